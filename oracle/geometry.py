@@ -1,0 +1,143 @@
+"""Panel discretisation of ellipse boundaries (oracle step O1).
+
+Section 2.1 gives the particles: centre a_i, director d_i = (cos th_i, sin th_i)
+parallel to the major axis, semi-axes a_i >= b_i.  Section 5 (Theorem
+qbx-accuracy) discretises the boundary with q-point composite Gauss-Legendre
+panels.
+
+Reading used here: the ellipse is parametrised counter-clockwise,
+    gamma(t) = a + R(th) (A cos t, B sin t),   t in [0, 2 pi),
+split into P equal-parameter panels [2 pi k / P, 2 pi (k+1) / P]; each panel
+carries the q Gauss-Legendre nodes of that interval.  The unit normal points
+out of the particle (into the water): nu = (gamma'_y, -gamma'_x) / |gamma'|.
+The quadrature weight of a node is w = (pi / P) omega_m |gamma'(t_m)|.
+Node order: particle, then panel (increasing t), then node (increasing t).
+"""
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+
+
+@dataclasses.dataclass
+class Params:
+    """Discretisation parameters.
+
+    panels: panels per particle;  q: Gauss-Legendre nodes per panel;
+    qbx_order: p, the local expansion keeps orders -p..p (section 5);
+    qbx_window: panels on each side of the target's own panel whose
+        contribution goes through the expansion;
+    qbx_nsub: sub-panels per window panel for the coefficient quadrature;
+    qbx_radius: expansion radius as a fraction of the target's panel length;
+    near_beta: a non-QBX panel J is near a target when the smallest distance
+        from the target to one of J's nodes is below near_beta * h_J;
+    near_nsub: sub-panels for the oversampled direct rule of such panels;
+    pot_nsub: sub-panels for off-surface targets closer than pot_beta * h_J.
+    """
+
+    panels: int = 16
+    q: int = 16
+    qbx_order: int = 8
+    qbx_nsub: int = 4
+    qbx_radius: float = 0.25
+    qbx_window: int = 2
+    near_beta: float = 0.5
+    near_nsub: int = 4
+    pot_nsub: int = 8
+    pot_beta: float = 0.5
+
+
+def gauss_legendre(q: int):
+    """Nodes (ascending) and weights of the q-point Gauss-Legendre rule on [-1, 1]."""
+    x, w = np.polynomial.legendre.leggauss(q)
+    return x, w
+
+
+def ellipse_eval(center, angle, axes, t):
+    """Position and derivative of gamma(t) for one ellipse; t an array."""
+    t = np.asarray(t, dtype=np.float64)
+    c, s = np.cos(angle), np.sin(angle)
+    ex, ey = axes[0] * np.cos(t), axes[1] * np.sin(t)
+    dx, dy = -axes[0] * np.sin(t), axes[1] * np.cos(t)
+    pos = np.stack([center[0] + c * ex - s * ey, center[1] + s * ex + c * ey], axis=-1)
+    der = np.stack([c * dx - s * dy, s * dx + c * dy], axis=-1)
+    return pos, der
+
+
+def normal_and_speed(der):
+    speed = np.hypot(der[..., 0], der[..., 1])
+    nrm = np.stack([der[..., 1], -der[..., 0]], axis=-1) / speed[..., None]
+    return nrm, speed
+
+
+@dataclasses.dataclass
+class Discretization:
+    x: np.ndarray        # (N, 2) node positions
+    normal: np.ndarray   # (N, 2) unit normals into the water
+    w: np.ndarray        # (N,)   quadrature weights (arclength)
+    t: np.ndarray        # (N,)   parameter values
+    particle: np.ndarray  # (N,) particle index
+    panel: np.ndarray    # (N,)   global panel index = particle * P + k
+    panel_h: np.ndarray  # (n*P,) panel arclengths (sum of the panel's weights)
+    params: Params
+    center: np.ndarray
+    angle: np.ndarray
+    axes: np.ndarray
+    kappa: float
+
+    @property
+    def N(self):
+        return self.x.shape[0]
+
+    @property
+    def n(self):
+        return self.center.shape[0]
+
+
+def panel_nodes(center, angle, axes, k, P, q, nsub=1):
+    """Nodes of panel k of one ellipse, optionally split into nsub equal sub-panels.
+
+    Returns positions (nsub*q, 2), normals, weights and the local coordinate of
+    every node in the coarse panel's [-1, 1] (used for interpolation).
+    """
+    xg, wg = gauss_legendre(q)
+    pos_l, nrm_l, w_l, xi_l = [], [], [], []
+    for s in range(nsub):
+        xi = -1.0 + (2.0 * s + (xg + 1.0)) / nsub          # coordinate in the coarse panel
+        t = 2.0 * np.pi / P * (k + (xi + 1.0) / 2.0)
+        pos, der = ellipse_eval(center, angle, axes, t)
+        nrm, speed = normal_and_speed(der)
+        pos_l.append(pos)
+        nrm_l.append(nrm)
+        w_l.append((np.pi / P / nsub) * wg * speed)
+        xi_l.append(xi)
+    return (np.concatenate(pos_l), np.concatenate(nrm_l), np.concatenate(w_l),
+            np.concatenate(xi_l))
+
+
+def discretize(particles, params: Params) -> Discretization:
+    """Discretise every ellipse of `particles` (any object with center/angle/axes/kappa)."""
+    P, q = params.panels, params.q
+    if P < 2 * params.qbx_window + 1:
+        raise ValueError("need at least 2*qbx_window+1 panels per particle")
+    xs, ns, ws, ts, pid, pan, hs = [], [], [], [], [], [], []
+    xg, wg = gauss_legendre(q)
+    for i in range(particles.center.shape[0]):
+        for k in range(P):
+            t = 2.0 * np.pi / P * (k + (xg + 1.0) / 2.0)
+            pos, der = ellipse_eval(particles.center[i], particles.angle[i], particles.axes[i], t)
+            nrm, speed = normal_and_speed(der)
+            w = (np.pi / P) * wg * speed
+            xs.append(pos)
+            ns.append(nrm)
+            ws.append(w)
+            ts.append(t)
+            pid.append(np.full(q, i))
+            pan.append(np.full(q, i * P + k))
+            hs.append(w.sum())
+    return Discretization(np.concatenate(xs), np.concatenate(ns), np.concatenate(ws),
+                          np.concatenate(ts), np.concatenate(pid), np.concatenate(pan),
+                          np.asarray(hs), params, np.asarray(particles.center, dtype=np.float64),
+                          np.asarray(particles.angle, dtype=np.float64),
+                          np.asarray(particles.axes, dtype=np.float64), float(particles.kappa))

@@ -1,0 +1,386 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+None of these re-types an oracle formula: each compares the oracle with a
+closed form, an identity, an independent quadrature or a brute-force sum.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy import integrate, special
+
+import oracle
+import workloads
+from oracle.geometry import Params, ellipse_eval, normal_and_speed
+
+
+def _disk_modes_ok(kap, P, p, n_list, tol):
+    d = oracle.discretize(workloads.single_disk(1.0, kap), Params(panels=P, qbx_order=p))
+    A = oracle.build_matrices(d)
+    th = np.arctan2(d.x[:, 1], d.x[:, 0])
+    for n in n_list:
+        # (1/2 I + D) e^{i n th} = kappa a I_n'(kappa a) K_n(kappa a) e^{i n th} on a disk
+        lam = kap * special.ivp(n, kap) * special.kv(n, kap)
+        v = np.cos(n * th)
+        assert np.abs(A @ v - lam * v).max() < tol, (kap, n)
+    return d, A
+
+
+# ---- geometry (section 2.1 ellipses, Gauss-Legendre panels) ------------------------------
+
+def test_gauss_legendre_exactness():
+    x, w = oracle.gauss_legendre(16)
+    for k in range(0, 32):
+        exact = 0.0 if k % 2 else 2.0 / (k + 1)
+        assert abs((w * x**k).sum() - exact) < 1e-14
+    assert np.all(np.diff(x) > 0)
+
+
+@pytest.mark.parametrize("A,B", [(1.0, 0.5), (1.2, 0.4), (1.0, 1.0)])
+def test_perimeter_area_normals(A, B):
+    p = workloads.Particles(np.array([[0.3, -0.7]]), np.array([0.9]), np.array([[A, B]]), 1.0)
+    d = oracle.discretize(p, Params(panels=32))
+    perim = 4 * A * special.ellipe(1 - (B / A) ** 2)
+    assert abs(d.w.sum() - perim) < 1e-13 * perim
+    # divergence theorem: area = 1/2 int x.nu ds
+    area = 0.5 * (d.w * ((d.x - p.center[0]) * d.normal).sum(1)).sum()
+    assert abs(area - math.pi * A * B) < 1e-13
+    assert np.allclose(np.hypot(d.normal[:, 0], d.normal[:, 1]), 1.0, atol=1e-15)
+    assert np.all(((d.x - p.center[0]) * d.normal).sum(1) > 0)    # out of the particle
+    assert np.all(np.diff(d.t) > 0)                                # node order: increasing t
+    assert np.allclose(d.panel_h.sum(), perim)
+
+
+def test_node_on_ellipse_and_director():
+    p = workloads.two_ellipses(3)
+    d = oracle.discretize(p, Params(panels=16))
+    for i in range(2):
+        m = d.particle == i
+        rel = d.x[m] - p.center[i]
+        c, s = math.cos(p.angle[i]), math.sin(p.angle[i])
+        u = c * rel[:, 0] + s * rel[:, 1]
+        v = -s * rel[:, 0] + c * rel[:, 1]
+        assert np.allclose((u / p.axes[i, 0]) ** 2 + (v / p.axes[i, 1]) ** 2, 1.0, atol=1e-14)
+        # first node lies just after t = 0, i.e. near the tip along the director
+        assert u[0] > 0.99 * p.axes[i, 0]
+
+
+# ---- special functions used by the oracle --------------------------------------------------
+
+def test_bessel_wronskian_and_mpmath():
+    mpmath = pytest.importorskip("mpmath")
+    mpmath.mp.dps = 40
+    for z in [1e-3, 0.05, 0.7, 2.0, 7.5, 30.0]:
+        for n in range(0, 12):
+            w = special.iv(n, z) * special.kv(n + 1, z) + special.iv(n + 1, z) * special.kv(n, z)
+            assert abs(w * z - 1.0) < 1e-13
+        for n in [0, 1, 5]:
+            assert abs(special.kv(n, z) / float(mpmath.besselk(n, z)) - 1) < 1e-14
+            assert abs(special.iv(n, z) / float(mpmath.besseli(n, z)) - 1) < 1e-14
+
+
+# ---- double layer: Gauss-type identities -----------------------------------------------------
+
+def test_dl_of_one_disk_closed_forms():
+    kap, a = 0.7, 1.3
+    d = oracle.discretize(workloads.single_disk(a, kap), Params(panels=32))
+    one = np.ones(d.N)
+    for R in [2.1, 3.0, 6.0]:
+        z = np.array([[R * math.cos(0.3), R * math.sin(0.3)]])
+        u = oracle.eval_potential(d, one, z)[0]
+        # D[1] = kappa a I1(kappa a) K0(kappa R) outside a disk
+        assert abs(u - kap * a * special.i1(kap * a) * special.k0(kap * R)) < 1e-13
+    uc = oracle.eval_potential(d, one, np.array([[0.0, 0.0]]))[0]
+    assert abs(uc + kap * a * special.k1(kap * a)) < 1e-13         # -kappa a K1(kappa a) at the centre
+
+
+def test_dl_laplace_limit_ellipse():
+    # kappa -> 0: D[1] is 0 outside and -1 inside (Gauss's lemma), for any closed curve
+    p = workloads.Particles(np.array([[0.0, 0.0]]), np.array([0.4]), np.array([[1.0, 0.5]]), 1e-7)
+    d = oracle.discretize(p, Params(panels=32))
+    one = np.ones(d.N)
+    assert abs(oracle.eval_potential(d, one, np.array([[0.1, 0.05]]))[0] + 1.0) < 1e-6
+    assert abs(oracle.eval_potential(d, one, np.array([[2.0, 1.0]]))[0]) < 1e-6
+
+
+def _ray_exit(A, B, x):
+    """Distance along direction phi from interior point x to the axis-aligned ellipse."""
+    def R(phi):
+        ux, uy = math.cos(phi), math.sin(phi)
+        a = (ux / A) ** 2 + (uy / B) ** 2
+        b = 2 * (x[0] * ux / A**2 + x[1] * uy / B**2)
+        c = (x[0] / A) ** 2 + (x[1] / B) ** 2 - 1
+        return (-b + math.sqrt(b * b - 4 * a * c)) / (2 * a)
+    return R
+
+
+def test_dl_of_one_ellipse_interior_area_identity():
+    # Green's identity for the Yukawa operator: for x inside P,
+    #   D[1](x) = kappa^2 int_P G(x, y) dy - 1,  and in polar coordinates about x
+    #   kappa^2/(2pi) int_0^R K0(kappa r) r dr = (1 - kappa R K1(kappa R)) / (2pi),
+    # so D[1](x) = -(1/2pi) int_0^{2pi} kappa R(phi) K1(kappa R(phi)) dphi.
+    kap, A, B = 0.8, 1.0, 0.5
+    p = workloads.Particles(np.array([[0.0, 0.0]]), np.array([0.0]), np.array([[A, B]]), kap)
+    d = oracle.discretize(p, Params(panels=32))
+    one = np.ones(d.N)
+    for x in [(0.0, 0.0), (0.4, 0.1), (-0.2, -0.25)]:
+        R = _ray_exit(A, B, x)
+        ref = -integrate.quad(lambda ph: kap * R(ph) * special.k1(kap * R(ph)), 0, 2 * np.pi,
+                              epsabs=1e-14, epsrel=1e-14, limit=200)[0] / (2 * np.pi)
+        u = oracle.eval_potential(d, one, np.array([x]))[0]
+        assert abs(u - ref) < 1e-11, x
+
+
+def test_dl_of_one_ellipse_exterior_area_identity():
+    # x outside P:  D[1](x) = kappa^2 int_P G(x, y) dy, by a tensor Gauss rule over the ellipse
+    kap, A, B = 1.3, 1.0, 0.5
+    p = workloads.Particles(np.array([[0.0, 0.0]]), np.array([0.0]), np.array([[A, B]]), kap)
+    d = oracle.discretize(p, Params(panels=32))
+    one = np.ones(d.N)
+    xr, wr = np.polynomial.legendre.leggauss(60)
+    xt, wt = np.polynomial.legendre.leggauss(120)
+    rr = 0.5 * (xr + 1)
+    tt = np.pi * (xt + 1)
+    Rg, Tg = np.meshgrid(rr, tt, indexing="ij")
+    W = np.outer(0.5 * wr, np.pi * wt) * A * B * Rg
+    Y = np.stack([A * Rg * np.cos(Tg), B * Rg * np.sin(Tg)], -1)
+    for x in [(1.8, 0.3), (0.2, 1.4), (-3.0, -1.0)]:
+        r = np.hypot(Y[..., 0] - x[0], Y[..., 1] - x[1])
+        ref = kap**2 * (W * special.k0(kap * r)).sum() / (2 * np.pi)
+        u = oracle.eval_potential(d, one, np.array([x]))[0]
+        assert abs(u - ref) < 1e-10, x
+
+
+# ---- QBX on-surface operator ------------------------------------------------------------------
+
+@pytest.mark.parametrize("kap", [0.25, 1.0, 2.0])
+def test_qbx_disk_eigenvalues(kap):
+    _disk_modes_ok(kap, 32, 10, [0, 1, 2, 5], 5e-11)
+
+
+def test_qbx_jump_relation_ellipse():
+    # exterior minus interior limit of D[sigma] is sigma (eq. djump)
+    p = workloads.Particles(np.array([[0.0, 0.0]]), np.array([0.3]), np.array([[1.0, 0.5]]), 1.0)
+    d = oracle.discretize(p, Params(panels=32, qbx_order=10))
+    sig = np.cos(2 * d.t) + 0.3 * np.sin(3 * d.t)
+    for i in [0, 37, 200, 511]:
+        pe, ve = oracle.qbx_row(d, i, side=1)
+        pi_, vi = oracle.qbx_row(d, i, side=-1)
+        jump = sum(ve[j] @ sig[J * 16:(J + 1) * 16] - vi[j] @ sig[J * 16:(J + 1) * 16]
+                   for j, J in enumerate(pe))
+        assert abs(jump - sig[i]) < 1e-9
+
+
+def test_qbx_ellipse_against_adaptive_quadrature():
+    # exterior limit = 1/2 sigma(x_i) + p.v. int dG/dnu sigma ds; on a smooth curve the
+    # double-layer integrand is bounded, so adaptive quadrature over the exact
+    # parametrisation (split at t_i) gives the principal value directly.
+    kap = 0.9
+    ctr, ang, ax = np.array([0.2, -0.1]), 0.7, np.array([1.0, 0.5])
+    p = workloads.Particles(ctr[None], np.array([ang]), ax[None], kap)
+    d = oracle.discretize(p, Params(panels=32, qbx_order=10))
+    sfun = lambda t: np.cos(2 * t) + 0.3 * np.sin(3 * t) + 0.2
+    sig = sfun(d.t)
+    rows = [0, 45, 130, 257, 400]
+    got = oracle.apply_rows(d, rows, sig)
+
+    def integrand(t, x):
+        pos, der = ellipse_eval(ctr, ang, ax, np.array([t]))
+        nrm, speed = normal_and_speed(der)
+        return (oracle.dl_kernel(x[None], pos, nrm, kap)[0] * speed[0] * sfun(t))
+
+    for a, i in enumerate(rows):
+        ti = d.t[i]
+        ref = 0.5 * sig[i] + sum(integrate.quad(integrand, lo, hi, args=(d.x[i],), epsabs=1e-14,
+                                                epsrel=1e-14, limit=400)[0]
+                                 for lo, hi in [(0.0, ti), (ti, 2 * np.pi)])
+        assert abs(got[a] - ref) < 2e-10, (i, got[a], ref)
+
+
+def test_gradient_disk_closed_form():
+    # density sigma = cos(n th)/lambda_n gives u = K_n(kappa r)/K_n(kappa a) cos(n th) outside
+    kap, n = 1.0, 3
+    d = oracle.discretize(workloads.single_disk(1.0, kap), Params(panels=32, qbx_order=10))
+    th = np.arctan2(d.x[:, 1], d.x[:, 0])
+    lam = kap * special.ivp(n, kap) * special.kv(n, kap)
+    sig = np.cos(n * th) / lam
+    rows = list(range(0, d.N, 37))
+    vals, grads = oracle.apply_rows(d, rows, sig, gradient=True)
+    ur = kap * special.kvp(n, kap) / special.kv(n, kap) * np.cos(n * th[rows])
+    ut = -n * np.sin(n * th[rows])
+    er = np.stack([np.cos(th[rows]), np.sin(th[rows])], 1)
+    et = np.stack([-np.sin(th[rows]), np.cos(th[rows])], 1)
+    assert np.abs(vals - np.cos(n * th[rows])).max() < 1e-10
+    assert np.abs((grads * er).sum(1) - ur).max() < 1e-8
+    assert np.abs((grads * et).sum(1) - ut).max() < 1e-8
+
+
+# ---- solve, potential, forces ---------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def point_source_problem():
+    # u = sum_k q_k G(x, s_k) with sources inside the particles solves eq. SL with f = u|Sigma
+    parts = workloads.Particles(np.array([[-1.3, 0.1], [1.25, -0.2], [0.1, 1.6]]),
+                                np.array([0.3, 2.0, -0.9]), np.array([[1.0, 0.5]] * 3), 0.8)
+    prm = Params(panels=12, qbx_order=10)
+    d = oracle.discretize(parts, prm)
+    src = parts.center + 0.2 * np.array([[1, 0], [0, 1], [-1, 0]])
+    qs = np.array([1.0, -0.6, 0.8])
+
+    def u_exact(x):
+        r = np.hypot(x[:, None, 0] - src[None, :, 0], x[:, None, 1] - src[None, :, 1])
+        return (special.k0(parts.kappa * r) / (2 * np.pi)) @ qs
+
+    def grad_exact(x):
+        dx = x[:, None, :] - src[None, :, :]
+        r = np.hypot(dx[..., 0], dx[..., 1])
+        c = -parts.kappa * special.k1(parts.kappa * r) / r / (2 * np.pi) * qs[None, :]
+        return (c[..., None] * dx).sum(1)
+
+    A, Gx, Gy = oracle.build_matrices(d, gradient=True)
+    f = u_exact(d.x)
+    sigma = oracle.lu_solve(A, f)
+    return dict(d=d, A=A, Gx=Gx, Gy=Gy, f=f, sigma=sigma, u=u_exact, g=grad_exact, parts=parts)
+
+
+def test_manufactured_solution_potential(point_source_problem):
+    P = point_source_problem
+    d = P["d"]
+    rng = np.random.default_rng(1)
+    pts = []
+    while len(pts) < 40:
+        z = rng.uniform(-3, 3, 2)
+        if np.min(np.hypot(*(d.x - z).T)) > 0.15:
+            # keep points outside every ellipse
+            inside = False
+            for c, th, ax in zip(d.center, d.angle, d.axes):
+                rel = z - c
+                u = math.cos(th) * rel[0] + math.sin(th) * rel[1]
+                v = -math.sin(th) * rel[0] + math.cos(th) * rel[1]
+                inside |= (u / ax[0]) ** 2 + (v / ax[1]) ** 2 < 1
+            if not inside:
+                pts.append(z)
+    pts = np.array(pts)
+    u = oracle.eval_potential(d, P["sigma"], pts)
+    assert np.abs(u - P["u"](pts)).max() < 1e-8
+
+
+def test_manufactured_solution_surface_gradient(point_source_problem):
+    P = point_source_problem
+    d = P["d"]
+    g = oracle.surface_fields(P["Gx"], P["Gy"], P["sigma"])
+    ge = P["g"](d.x)
+    assert np.abs(g - ge).max() < 5e-6 * np.abs(ge).max()
+
+
+def test_gmres_matches_lu(point_source_problem):
+    P = point_source_problem
+    x, its, hist = oracle.gmres(lambda v: P["A"] @ v, P["f"], tol=1e-13, maxiter=100)
+    assert np.abs(x - P["sigma"]).max() < 1e-11 * np.abs(P["sigma"]).max()
+    assert its < 40                       # second-kind: few iterations
+    assert hist[-1] <= 1e-13
+
+
+def test_isolated_disk_forces_and_energy():
+    # eq. true_soln: f = 1/2 (1 + cos th) on a disk of radius a, rho = 4a; an isolated
+    # particle feels no net force or torque (eq. net), and
+    # Phi = -gamma/kappa int f du/dr ds = -(gamma a pi / (2 kappa)) kappa [K0'/K0 + 1/2 K1'/K1]
+    a, kap = 1.0, 0.25
+    d = oracle.discretize(workloads.single_disk(a, kap), Params(panels=16, qbx_order=8))
+    f = oracle.janus_label(d, 2)
+    A, Gx, Gy = oracle.build_matrices(d, gradient=True)
+    sigma = oracle.lu_solve(A, f)
+    g = oracle.surface_fields(Gx, Gy, sigma)
+    F, tau, tau0, E = oracle.forces_torques(d, f, g, gamma=1.0)
+    # the paper reports these integrals as zero "to about eight digits" (section S2.2)
+    assert np.abs(F).max() < 5e-8 and abs(tau[0]) < 5e-8
+    z = kap * a
+    Eref = -(a * math.pi / 2) * (special.kvp(0, z) / special.k0(z) + 0.5 * special.kvp(1, z) / special.k1(z))
+    assert abs(E - Eref) < 1e-7 * abs(Eref)
+    # off-surface u against eq. true_soln (rho = 4a)
+    rng = np.random.default_rng(0)
+    r = rng.uniform(1.2, 2.5, 30)
+    t = rng.uniform(-np.pi, np.pi, 30)
+    pts = np.stack([r * np.cos(t), r * np.sin(t)], 1)
+    ref = 0.5 * (special.k0(r * kap) / special.k0(a * kap) + special.k1(r * kap) / special.k1(a * kap) * np.cos(t))
+    assert np.abs(oracle.eval_potential(d, sigma, pts) - ref).max() < 1e-9
+
+
+def test_net_force_torque_free_and_bounds(point_source_problem):
+    # eq. net: sum F_i = 0 and sum tau0_i = 0 for any configuration and label;
+    # maximum principle 0 <= u <= 1 for f in [0, 1] and decay u < 2 exp(-D/rho) (eq. exp_decay)
+    # (the smooth Janus label; the tanh arc's 0.1 rad edges are not resolved by 12 panels)
+    P = point_source_problem
+    d = P["d"]
+    f = oracle.janus_label(d, 4)
+    sigma = oracle.lu_solve(P["A"], f)
+    g = oracle.surface_fields(P["Gx"], P["Gy"], sigma)
+    F, tau, tau0, E = oracle.forces_torques(d, f, g)
+    scale = np.abs(F).max()
+    assert scale > 1e-3
+    assert np.abs(F.sum(0)).max() < 1e-6 * scale
+    assert abs(tau0.sum()) < 1e-6 * max(np.abs(tau0).max(), 1e-12)
+    assert E > 0
+    f = oracle.arc_label(d)
+    sigma = oracle.lu_solve(P["A"], f)
+    rng = np.random.default_rng(2)
+    pts = rng.uniform(-4, 4, (300, 2))
+    dist = np.array([np.min(np.hypot(*(d.x - z).T)) for z in pts])
+    pts = pts[dist > 0.3]
+    # drop points inside particles
+    keep = []
+    for z in pts:
+        ok = True
+        for c, th, ax in zip(d.center, d.angle, d.axes):
+            rel = z - c
+            u = math.cos(th) * rel[0] + math.sin(th) * rel[1]
+            v = -math.sin(th) * rel[0] + math.cos(th) * rel[1]
+            ok &= (u / ax[0]) ** 2 + (v / ax[1]) ** 2 > 1
+        keep.append(ok)
+    pts = pts[np.array(keep)]
+    u = oracle.eval_potential(d, sigma, pts)
+    assert u.min() > -1e-9 and u.max() < 1 + 1e-9
+    far = np.array([[40.0, 0.0]])
+    D = 40.0 - 2.5
+    assert abs(oracle.eval_potential(d, sigma, far)[0]) < 2 * math.exp(-D * d.kappa)
+
+
+@pytest.mark.slow
+def test_centred_difference_force_and_torque():
+    # eq. pos_test: v.F_i = -dPhi/de along a_i + e v and tau_i = -dPhi/de along th_i + e,
+    # with Richardson extrapolation of two step sizes.
+    base = workloads.Particles(np.array([[-1.2, 0.0], [1.3, 0.4]]), np.array([0.3, 2.5]),
+                               np.array([[1.0, 0.5]] * 2), 1.0)
+    prm = Params(panels=12, qbx_order=10)
+
+    def solve(parts, gradient=False):
+        d = oracle.discretize(parts, prm)
+        f = oracle.janus_label(d, 4)
+        if gradient:
+            A, Gx, Gy = oracle.build_matrices(d, gradient=True)
+            s = oracle.lu_solve(A, f)
+            return oracle.forces_torques(d, f, oracle.surface_fields(Gx, Gy, s))
+        A, Gx, Gy = oracle.build_matrices(d, gradient=True)
+        s = oracle.lu_solve(A, f)
+        return oracle.forces_torques(d, f, oracle.surface_fields(Gx, Gy, s))[3]
+
+    F, tau, _, _ = solve(base, gradient=True)
+
+    def dphi(move, e):
+        pp, pm = base.copy(), base.copy()
+        move(pp, e)
+        move(pm, -e)
+        return (solve(pp) - solve(pm)) / (2 * e)
+
+    def rich(move):
+        e = 0.02
+        return (4 * dphi(move, e / 2) - dphi(move, e)) / 3
+
+    def mx(p, e):
+        p.center[0, 0] += e
+
+    def rot(p, e):
+        p.angle[1] += e
+
+    assert abs(-rich(mx) - F[0, 0]) < 1e-5 * max(1.0, abs(F[0, 0]))
+    assert abs(-rich(rot) - tau[1]) < 1e-5 * max(1.0, abs(tau[1]))

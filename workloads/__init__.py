@@ -1,0 +1,217 @@
+"""Seeded synthetic particle ensembles.
+
+This module only draws inputs: ellipse centres, orientations, semi-axes,
+screening constants and random densities.  It holds none of the integral
+equation arithmetic, so both the HIP path and the CPU oracle can be fed from
+it without sharing any of the method.
+
+The ensembles follow the paper's large-collection experiments (random,
+non-overlapping particles in an Lx x Ly box, section S2.5, Table 2) with the
+ellipse shapes of section 2.1 (centre a_i, director angle theta_i along the
+major axis, semi-axes a_i >= b_i).
+
+Placement recipe (rejection sampling, numpy ``default_rng(seed)``):
+  * centre uniform in [A_max + margin, L - A_max - margin]^2, angle U[0, 2pi),
+  * accept when the sampled boundary-to-boundary distance to every placed
+    ellipse, minus the sampling resolution, is at least ``gap``.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Optional
+
+import numpy as np
+
+__all__ = [
+    "Particles",
+    "two_ellipses",
+    "random_ellipses",
+    "config_small",
+    "config_medium",
+    "config_large",
+    "batched_configs",
+    "serving_trace",
+    "single_disk",
+    "random_density",
+]
+
+_NSAMPLE = 256  # boundary samples per ellipse for the overlap test
+
+
+@dataclasses.dataclass
+class Particles:
+    """A set of rigid ellipses.
+
+    center: (n, 2) centres a_i;  angle: (n,) director angles theta_i (the
+    director d_i = (cos, sin) is parallel to the major axis);  axes: (n, 2)
+    semi-axes (A_i, B_i) with A_i along d_i.  kappa = 1/rho is the inverse
+    screening length.
+    """
+
+    center: np.ndarray
+    angle: np.ndarray
+    axes: np.ndarray
+    kappa: float
+    name: str = ""
+
+    @property
+    def n(self) -> int:
+        return int(self.center.shape[0])
+
+    def copy(self) -> "Particles":
+        return Particles(self.center.copy(), self.angle.copy(), self.axes.copy(),
+                         float(self.kappa), self.name)
+
+
+def _boundary_samples(center, angle, axes, m=_NSAMPLE):
+    t = np.linspace(0.0, 2.0 * np.pi, m, endpoint=False)
+    c, s = math.cos(angle), math.sin(angle)
+    ex = axes[0] * np.cos(t)
+    ey = axes[1] * np.sin(t)
+    return np.stack([center[0] + c * ex - s * ey, center[1] + s * ex + c * ey], axis=1)
+
+
+def _sample_spacing(axes, m=_NSAMPLE):
+    # the largest chord between consecutive samples is at most A * 2pi/m
+    return float(axes[0]) * 2.0 * np.pi / m
+
+
+def _place(rng, n, box, axes_fn, gap, max_tries=200000):
+    centers: List[np.ndarray] = []
+    angles: List[float] = []
+    axes: List[np.ndarray] = []
+    samples: List[np.ndarray] = []
+    tries = 0
+    while len(centers) < n:
+        tries += 1
+        if tries > max_tries:
+            raise RuntimeError(f"could not place {n} ellipses in box {box} (placed {len(centers)})")
+        ax = np.asarray(axes_fn(rng), dtype=np.float64)
+        lo = ax[0] + 0.5 * gap
+        c = rng.uniform(lo, box - lo, size=2)
+        th = rng.uniform(0.0, 2.0 * np.pi)
+        ok = True
+        if centers:
+            C = np.asarray(centers)
+            A = np.asarray(axes)[:, 0]
+            d = np.hypot(C[:, 0] - c[0], C[:, 1] - c[1])
+            cand = np.nonzero(d < A + ax[0] + gap + 1e-6)[0]
+            if cand.size:
+                sp = _boundary_samples(c, th, ax)
+                for j in cand:
+                    dd = np.sqrt(((sp[:, None, :] - samples[j][None, :, :]) ** 2).sum(-1)).min()
+                    slack = 0.5 * (_sample_spacing(ax) + _sample_spacing(axes[j]))
+                    # the sampled minimum can only overestimate the true one
+                    if dd - slack < gap + 1e-3:
+                        ok = False
+                        break
+        if ok:
+            centers.append(c)
+            angles.append(th)
+            axes.append(ax)
+            samples.append(_boundary_samples(c, th, ax))
+    return np.asarray(centers), np.asarray(angles), np.asarray(axes)
+
+
+def random_ellipses(n: int, box: float, kappa: float, seed: int, gap: float = 0.2,
+                    axes=(1.0, 0.5), axes_range=None, name: str = "") -> Particles:
+    """n ellipses at random non-overlapping positions in a box x box square.
+
+    axes: fixed semi-axes (A, B); or axes_range=((Alo, Ahi), (Blo, Bhi)) draws
+    A and B uniformly per particle.
+    """
+    rng = np.random.default_rng(seed)
+    if axes_range is None:
+        fixed = np.asarray(axes, dtype=np.float64)
+        axes_fn = lambda r: fixed
+    else:
+        (alo, ahi), (blo, bhi) = axes_range
+        axes_fn = lambda r: np.array([r.uniform(alo, ahi), r.uniform(blo, bhi)])
+    c, th, ax = _place(rng, n, box, axes_fn, gap)
+    return Particles(c, th, ax, float(kappa), name or f"{n} ellipses, box {box}, seed {seed}")
+
+
+def two_ellipses(seed: int = 0, kappa: float = 1.0) -> Particles:
+    """Two 1.0 x 0.5 ellipses with centres 2.5 apart and random orientations."""
+    rng = np.random.default_rng(seed)
+    center = np.array([[-1.25, 0.0], [1.25, 0.0]])
+    angle = rng.uniform(0.0, 2.0 * np.pi, size=2)
+    axes = np.array([[1.0, 0.5], [1.0, 0.5]])
+    return Particles(center, angle, axes, float(kappa), f"2 ellipses, seed {seed}")
+
+
+def single_disk(radius: float = 1.0, kappa: float = 0.25, angle: float = 0.0,
+                center=(0.0, 0.0)) -> Particles:
+    """One disk of the given radius (the single-particle validation, section S2.2)."""
+    return Particles(np.array([list(center)], dtype=np.float64), np.array([angle]),
+                     np.array([[radius, radius]]), float(kappa), "disk")
+
+
+# --- the named workloads -------------------------------------------------------------------
+
+def config_small(seed: int = 0) -> dict:
+    """2 ellipses 1.0x0.5, 16 panels x 16 nodes (N=512), kappa=1, QBX order 8."""
+    return dict(particles=two_ellipses(seed, 1.0), panels=16, qbx_order=8, tol=1e-10,
+                name="2 ellipses N=512")
+
+
+def config_medium(kappa: float = 1.0, seed: int = 0) -> dict:
+    """50 ellipses 1.0x0.5 in a 30x30 box, gap 0.2, 32 panels x 16 nodes (N=25,600), QBX order 10."""
+    p = random_ellipses(50, 30.0, kappa, seed, gap=0.2)
+    return dict(particles=p, panels=32, qbx_order=10, tol=1e-8,
+                name=f"50 ellipses N=25600 kappa={kappa:g}")
+
+
+def config_large(seed: int = 0) -> dict:
+    """500 ellipses, A~U[0.8,1.2], B~U[0.4,0.6], 100x100 box, N=256,000, QBX order 10."""
+    p = random_ellipses(500, 100.0, 1.0, seed, gap=0.2, axes_range=((0.8, 1.2), (0.4, 0.6)))
+    return dict(particles=p, panels=32, qbx_order=10, tol=1e-8, fmm_order=20, fmm_leaf=64,
+                name="500 ellipses N=256000")
+
+
+def batched_configs(count: int, seed: int = 0, nmin: int = 10, nmax: int = 200,
+                    kappa_range=(0.5, 2.0)) -> List[Particles]:
+    """`count` independent configurations with log-uniform particle counts in [nmin, nmax].
+
+    Box side L = 30 sqrt(n/50) keeps the 50-in-30x30 density; kappa ~ U(kappa_range).
+    """
+    rng = np.random.default_rng(seed)
+    out = []
+    for c in range(count):
+        n = int(round(math.exp(rng.uniform(math.log(nmin), math.log(nmax)))))
+        kappa = float(rng.uniform(*kappa_range))
+        box = 30.0 * math.sqrt(n / 50.0)
+        out.append(random_ellipses(n, box, kappa, seed=int(rng.integers(2**31)), gap=0.2,
+                                   name=f"batch {c}: {n} ellipses"))
+    return out
+
+
+def serving_trace(count: int, rate: float = 200.0, seed: int = 0, nmin: int = 10,
+                  nmax: int = 2000, kappa_range=(0.5, 2.0)) -> List[dict]:
+    """A Poisson arrival trace of solve requests.
+
+    Each request: arrival time (s), particle count log-uniform in [nmin, nmax],
+    kappa ~ U(kappa_range), and the seed of its layout (drawn lazily with
+    `trace_particles`).
+    """
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for k in range(count):
+        t += float(rng.exponential(1.0 / rate))
+        n = int(round(math.exp(rng.uniform(math.log(nmin), math.log(nmax)))))
+        out.append(dict(id=k, arrival=t, n=n, kappa=float(rng.uniform(*kappa_range)),
+                        seed=int(rng.integers(2**31))))
+    return out
+
+
+def trace_particles(req: dict) -> Particles:
+    n = req["n"]
+    return random_ellipses(n, 30.0 * math.sqrt(n / 50.0), req["kappa"], req["seed"], gap=0.2,
+                           name=f"request {req['id']}: {n} ellipses")
+
+
+def random_density(N: int, seed: int) -> np.ndarray:
+    """A seeded random density vector (for operator tests)."""
+    return np.random.default_rng(seed).standard_normal(N)
