@@ -1,0 +1,192 @@
+/*
+ * yqbx: screened-Laplace (Yukawa) double-layer solver for many rigid ellipses
+ * on one AMD Instinct MI355X (gfx950).
+ *
+ * The problem (Fu, Ryham, Kloeckner, Wala, Jiang, Young, arXiv 1810.04131):
+ *   exterior Dirichlet problem  -rho^2 Lap u + u = 0 in the water,  u = f on the
+ *   particle boundaries Sigma,  u -> 0 at infinity                   (eq. SL),
+ *   represented as u = D[sigma] (eq. intrep) with G = K0(|x-y|/rho)/(2 pi)
+ *   (eq. Gfunc) and solved through the second-kind equation
+ *   1/2 sigma + D sigma = f                                          (eq. bie).
+ *   Discretisation: Nystrom on 16-point Gauss-Legendre panels, QBX local
+ *   expansions from Graf's addition theorem near the target (section 5, eqs.
+ *   local-exp, graf-coefficient, graf-addition), tiled direct far field.
+ *   Outputs: density sigma, surface gradient, hydrophobic forces and torques
+ *   (eqs. stress, force_torque, scalar-torque) and the energy of eq. main.
+ *
+ * Conventions for every entry point
+ *   - kappa = 1/rho.  Lengths in the caller's units; gamma (eq. main) scales
+ *     forces, torques and energy linearly.
+ *   - Particles are ellipses: centre a_i, director angle th_i (the major axis
+ *     points along (cos th_i, sin th_i), section 2.1), semi-axes A_i >= B_i.
+ *   - Nodes are ordered particle-major, then panel (counter-clockwise from the
+ *     director, i.e. increasing t in a_i + R(th_i)(A cos t, B sin t)), then
+ *     Gauss-Legendre node (increasing t).  N = n * panels_per_particle * 16.
+ *     The unit normal points out of the particle into the water.
+ *   - Arrays named "host" are caller-owned host memory.  Arrays named "dev"
+ *     are caller-owned device memory of the current HIP device, laid out as
+ *     plain contiguous doubles; the library only reads/writes them during the
+ *     call or, for the asynchronous entry points, in stream order on the
+ *     problem's stream.  The library owns all of its own device memory.
+ *   - Every call returns a status (YQ_OK = 0 or a negative code).  No C++
+ *     exception crosses the ABI.  yq_last_error() gives a message.
+ *   - One thread at a time per problem handle.
+ */
+#ifndef YQBX_H
+#define YQBX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  YQ_OK = 0,
+  YQ_EINVAL = -1,   /* invalid argument: null pointer, size or parameter out of range */
+  YQ_EGEOM = -2,    /* geometry rejected: particles overlap or a node lies inside another particle */
+  YQ_ENOCONV = -3,  /* GMRES reached maxiter above tolerance; outputs are still written */
+  YQ_ENOMEM = -4,   /* device memory allocation failed */
+  YQ_EDEVICE = -5,  /* HIP runtime error */
+  YQ_ESTATE = -6,   /* call out of order, e.g. a solve before yq_set_particles */
+  YQ_EADMIT = -7    /* serving: request larger than the device-memory budget */
+};
+
+enum { YQ_FP64 = 0, YQ_MIXED = 1 };                       /* precision */
+enum { YQ_FAR_DIRECT = 0, YQ_FAR_FMM = 1, YQ_FAR_AUTO = 2 };   /* far-field mode */
+enum { YQ_LABEL_ARC = 0, YQ_LABEL_JANUS = 1 };             /* boundary labels */
+
+typedef struct yq_problem yq_problem;
+
+typedef struct yq_params {
+  int32_t panels_per_particle; /* P; equal-parameter panels of 16 nodes, P >= 2*qbx_window+1 */
+  int32_t qbx_order;           /* p: the local expansion keeps orders -p..p (section 5), 1..30 */
+  int32_t qbx_window;          /* panels on each side of the target's panel taken through the expansion */
+  int32_t qbx_oversample;      /* sub-panels per window panel for the coefficient quadrature (1..8) */
+  double qbx_radius;           /* expansion radius / arclength of the target's panel */
+  double near_beta;            /* other panels closer than near_beta*h (nearest node) are oversampled */
+  int32_t near_oversample;     /* sub-panels for those panels (1..8) */
+  int32_t pot_oversample;      /* sub-panels for off-surface targets near a panel (1..16) */
+  double pot_beta;             /* off-surface near criterion, as near_beta */
+  int32_t precision;           /* YQ_FP64, or YQ_MIXED: FP32 far field inside FP64 refinement */
+  int32_t far_mode;            /* YQ_FAR_DIRECT | YQ_FAR_FMM | YQ_FAR_AUTO */
+  int32_t fmm_order;           /* FMM expansion order (far_mode FMM) */
+  int32_t fmm_leaf_max;        /* nodes per quadtree leaf (far_mode FMM) */
+  double tol;                  /* GMRES: stop at ||f - A sigma||_2 / ||f||_2 <= tol */
+  int32_t maxiter;             /* GMRES: total inner iterations */
+  int32_t restart;             /* GMRES: Krylov dimension before a restart (<= 200) */
+  double inner_tol;            /* YQ_MIXED: relative tolerance of each FP32-operator inner solve */
+  int32_t max_refine;          /* YQ_MIXED: maximum refinement (outer) steps */
+} yq_params;
+
+typedef struct yq_solve_info {
+  int32_t iterations;       /* total inner GMRES iterations */
+  int32_t outer_steps;      /* refinement steps (YQ_MIXED) or restart cycles (YQ_FP64) */
+  int32_t matvecs_fp64;     /* FP64 operator applications */
+  int32_t matvecs_fp32;     /* FP32-far-field operator applications */
+  double residual;          /* final true relative residual with the FP64 operator */
+  double seconds;           /* wall time of the solve */
+} yq_solve_info;
+
+/* Defaults: P = 32, p = 10, window 2, oversample 4, radius 0.25, near_beta 0.5,
+ * near_oversample 4, pot_oversample 8, pot_beta 0.5, FP64, direct far field,
+ * FMM order 20 / 64 per leaf, tol 1e-10, maxiter 200, restart 100,
+ * inner_tol 1e-6, max_refine 8. */
+void yq_default_params(yq_params* params);
+
+/* Creates a problem on the current HIP device.  params: host, copied. */
+int yq_create(const yq_params* params, yq_problem** out);
+void yq_destroy(yq_problem* prob);
+
+/* Status text, and the last detailed message of a problem (NULL: of the calling thread). */
+const char* yq_error_string(int status);
+const char* yq_last_error(const yq_problem* prob);
+
+/* All later work of the problem is issued on this HIP stream (hipStream_t; NULL = default). */
+int yq_set_stream(yq_problem* prob, void* hip_stream);
+
+/* Geometry and set-up (steps a1 geometry, a3 QBX centres and near lists,
+ * a4 QBX correction build; section 2.1 particles, section 5 discretisation).
+ * center_xy: host [2n] (x0,y0,x1,y1,...); angle: host [n] director angles;
+ * semi_axes: host [2n] (A0,B0,A1,B1,...), A >= B > 0; kappa > 0.
+ * Builds nodes, normals, weights, near lists and the FP64 QBX correction of
+ * the operator and of its surface gradient.  Synchronous.
+ * YQ_EGEOM if a node of one particle lies inside another. */
+int yq_set_particles(yq_problem* prob, int32_t n, const double* center_xy, const double* angle,
+                     const double* semi_axes, double kappa);
+
+int yq_num_nodes(const yq_problem* prob, int64_t* N);
+int yq_num_particles(const yq_problem* prob, int32_t* n);
+
+/* Node data (step a1): dev x,y,nx,ny,w each [N] (any may be NULL).  Synchronous. */
+int yq_get_nodes(const yq_problem* prob, double* x, double* y, double* nx, double* ny, double* w);
+
+/* Extra near panels (step a3): panels outside a target's QBX window whose
+ * nearest node is closer than near_beta * h.  yq_near_count gives their total;
+ * yq_get_near fills dev row_ptr [N+1] and dev panels [total] (global panel
+ * index = particle * P + k), rows in node order, panels ascending. */
+int yq_near_count(const yq_problem* prob, int64_t* total);
+int yq_get_near(const yq_problem* prob, int32_t* row_ptr, int32_t* panels);
+
+/* Boundary labels (step a2): writes dev f [N].  YQ_LABEL_ARC: smoothed arc
+ * f = 1/2 [tanh((phi+a)/b) - tanh((phi-a)/b)], a = param0 (half opening),
+ * b = param1 (edge width), phi in (-pi, pi] the polar angle from the director.
+ * YQ_LABEL_JANUS: f = 1 - sin^p(phi/2), p = param0 (eq. JanusBC, read with
+ * phi/2 so that head and tail differ).  Synchronous. */
+int yq_boundary_label(yq_problem* prob, int32_t kind, double param0, double param1, double* f);
+
+/* Sets the Dirichlet data f (dev [N], copied). */
+int yq_set_boundary_data(yq_problem* prob, const double* f);
+
+/* Far field alone (step a5): out_i = sum_{j != i} w_j dG/dnu_y(x_i, y_j) sigma_j
+ * over every node pair, in FP64 (YQ_FP64) or FP32 arithmetic (YQ_MIXED).
+ * dev sigma [N], dev out [N].  Asynchronous on the problem's stream. */
+int yq_apply_far(yq_problem* prob, const double* sigma, double* out, int32_t precision);
+
+/* The discrete operator (steps a5 + a6): out = (1/2 I + D) sigma with the
+ * QBX near correction (eq. bie).  dev sigma [N], dev out [N] (must not alias).
+ * Asynchronous on the problem's stream. */
+int yq_apply_operator(yq_problem* prob, const double* sigma, double* out, int32_t precision);
+
+/* GMRES solve of eq. bie for the data set by yq_set_boundary_data (steps a8,
+ * a9).  dev sigma0 [N] initial guess or NULL (zero); dev sigma [N] result;
+ * info: host, may be NULL.  Synchronous.  YQ_ENOCONV: not converged (sigma
+ * holds the last iterate). */
+int yq_solve(yq_problem* prob, const double* sigma0, double* sigma, yq_solve_info* info);
+
+/* Exterior-limit surface gradient of u = D[sigma] at the nodes (step a10):
+ * dev gx, gy [N].  Asynchronous. */
+int yq_surface_gradient(yq_problem* prob, const double* sigma, double* gx, double* gy);
+
+/* Hydrophobic forces and torques (step a11, eqs. stress, force_torque,
+ * scalar-torque): u = f on Sigma, grad u from yq_surface_gradient.
+ * dev force [2n] (Fx0,Fy0,...), dev torque [n] about each centre a_i,
+ * host energy (may be NULL): Phi = -gamma/kappa int f du/dnu ds.  Synchronous. */
+int yq_forces(yq_problem* prob, const double* sigma, double gamma, double* force, double* torque,
+              double* energy);
+
+/* Off-surface potential u = D[sigma] (step a12, eq. intrep) at M targets:
+ * dev tx, ty [M], dev u [M].  Panels whose nearest node is closer than
+ * pot_beta*h use a pot_oversample-fold oversampled rule.  Asynchronous. */
+int yq_eval_potential(yq_problem* prob, const double* sigma, int64_t M, const double* tx,
+                      const double* ty, double* u);
+
+/* Per-phase GPU timers: with profiling enabled every launch of a phase is
+ * bracketed by hipEvents on the problem's stream.  Phases: 0 FP64 far field,
+ * 1 FP32 far field, 2 finish (chunk sum + near correction), 3 gradient far
+ * field, 4 QBX build, 5 Krylov vector kernels.  yq_profile_read synchronises
+ * the stream and returns the number of timed launches and their summed
+ * duration (ms) of one phase; reset != 0 clears that phase. */
+int yq_profile_enable(yq_problem* prob, int32_t enable);
+int yq_profile_read(yq_problem* prob, int32_t phase, int64_t* launches, double* total_ms,
+                    int32_t reset);
+
+/* Device special functions (L0), for testing: kind 0 -> K0(z), 1 -> K1(z),
+ * 2 -> K_order(z), 3 -> I_order(z); precision YQ_FP64 or YQ_MIXED (FP32).
+ * dev z [n] -> dev out [n].  Synchronous. */
+int yq_bessel(int32_t kind, int32_t order, int32_t precision, int64_t n, const double* z, double* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* YQBX_H */

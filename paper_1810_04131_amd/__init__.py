@@ -1,0 +1,178 @@
+"""yqbx: MI355X-native Yukawa double-layer solver for many rigid ellipses.
+
+Python binding of the C ABI in include/yqbx.h.  Every step of the solve runs
+in the HIP library (libyqbx.so); this module only marshals arguments and uses
+PyTorch for device memory and the current stream.  There is no CPU fallback:
+the functions raise when the library is missing or no GPU is present.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional
+
+from . import _lib
+from ._lib import (YQ_FAR_AUTO, YQ_FAR_DIRECT, YQ_FAR_FMM, YQ_FP64, YQ_LABEL_ARC,  # noqa: F401
+                   YQ_LABEL_JANUS, YQ_MIXED, YQError, yq_params, yq_solve_info)
+
+__all__ = ["Problem", "default_params", "bessel", "YQError", "YQ_FP64", "YQ_MIXED"]
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("yqbx needs a ROCm GPU (torch.cuda.is_available() is False)")
+    return torch
+
+
+def default_params(**overrides) -> yq_params:
+    lib = _lib.load()
+    p = yq_params()
+    lib.yq_default_params(ctypes.byref(p))
+    for k, v in overrides.items():
+        if not hasattr(p, k):
+            raise KeyError(k)
+        setattr(p, k, v)
+    return p
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+class Problem:
+    """One particle configuration on one GPU (a yq_problem handle)."""
+
+    def __init__(self, params: Optional[yq_params] = None, device: str = "cuda:0", **overrides):
+        torch = _torch()
+        self.torch = torch
+        self.device = torch.device(device)
+        torch.cuda.set_device(self.device)
+        self.lib = _lib.load()
+        self.params = params if params is not None else default_params(**overrides)
+        h = ctypes.c_void_p()
+        _lib.check(self.lib.yq_create(ctypes.byref(self.params), ctypes.byref(h)))
+        self.h = h
+        self.stream = torch.cuda.current_stream(self.device)
+        self._check(self.lib.yq_set_stream(self.h, ctypes.c_void_p(self.stream.cuda_stream)))
+        self.n = 0
+        self.N = 0
+
+    def _check(self, st):
+        return _lib.check(st, self.h)
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            self.lib.yq_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _f64(self, *shape):
+        return self.torch.empty(*shape, dtype=self.torch.float64, device=self.device)
+
+    def _dev(self, t):
+        t = self.torch.as_tensor(t, dtype=self.torch.float64, device=self.device)
+        return t.contiguous()
+
+    # -- set-up ---------------------------------------------------------------------------
+    def set_particles(self, center, angle, axes, kappa):
+        import numpy as np
+        c = np.ascontiguousarray(np.asarray(center, dtype=np.float64).reshape(-1))
+        a = np.ascontiguousarray(np.asarray(angle, dtype=np.float64).reshape(-1))
+        x = np.ascontiguousarray(np.asarray(axes, dtype=np.float64).reshape(-1))
+        n = a.size
+        self._check(self.lib.yq_set_particles(self.h, n, c.ctypes.data_as(ctypes.c_void_p),
+                                              a.ctypes.data_as(ctypes.c_void_p),
+                                              x.ctypes.data_as(ctypes.c_void_p), float(kappa)))
+        N = ctypes.c_int64()
+        self._check(self.lib.yq_num_nodes(self.h, ctypes.byref(N)))
+        self.n, self.N = n, int(N.value)
+        return self
+
+    def set_workload(self, particles):
+        return self.set_particles(particles.center, particles.angle, particles.axes, particles.kappa)
+
+    def nodes(self):
+        out = [self._f64(self.N) for _ in range(5)]
+        self._check(self.lib.yq_get_nodes(self.h, *[_ptr(t) for t in out]))
+        return dict(zip(["x", "y", "nx", "ny", "w"], out))
+
+    def near(self):
+        tot = ctypes.c_int64()
+        self._check(self.lib.yq_near_count(self.h, ctypes.byref(tot)))
+        rp = self.torch.empty(self.N + 1, dtype=self.torch.int32, device=self.device)
+        pn = self.torch.empty(max(int(tot.value), 1), dtype=self.torch.int32, device=self.device)
+        self._check(self.lib.yq_get_near(self.h, _ptr(rp), _ptr(pn)))
+        return rp, pn[: int(tot.value)]
+
+    def boundary_label(self, kind=YQ_LABEL_ARC, a=0.7853981633974483, b=0.1):
+        f = self._f64(self.N)
+        self._check(self.lib.yq_boundary_label(self.h, kind, float(a), float(b), _ptr(f)))
+        return f
+
+    def set_boundary_data(self, f):
+        f = self._dev(f)
+        self._check(self.lib.yq_set_boundary_data(self.h, _ptr(f)))
+        self._f = f
+        return self
+
+    # -- operator and solve ---------------------------------------------------------------
+    def apply_far(self, sigma, precision=YQ_FP64, out=None):
+        sigma = self._dev(sigma)
+        out = self._f64(self.N) if out is None else out
+        self._check(self.lib.yq_apply_far(self.h, _ptr(sigma), _ptr(out), precision))
+        return out
+
+    def apply_operator(self, sigma, precision=YQ_FP64, out=None):
+        sigma = self._dev(sigma)
+        out = self._f64(self.N) if out is None else out
+        self._check(self.lib.yq_apply_operator(self.h, _ptr(sigma), _ptr(out), precision))
+        return out
+
+    def solve(self, sigma0=None, out=None, allow_noconv=False):
+        s0 = self._dev(sigma0) if sigma0 is not None else None
+        out = self._f64(self.N) if out is None else out
+        info = yq_solve_info()
+        st = self.lib.yq_solve(self.h, _ptr(s0), _ptr(out), ctypes.byref(info))
+        if not (allow_noconv and st == _lib.YQ_ENOCONV):
+            self._check(st)
+        return out, {k: getattr(info, k) for k, _ in info._fields_}
+
+    def surface_gradient(self, sigma):
+        sigma = self._dev(sigma)
+        gx, gy = self._f64(self.N), self._f64(self.N)
+        self._check(self.lib.yq_surface_gradient(self.h, _ptr(sigma), _ptr(gx), _ptr(gy)))
+        return gx, gy
+
+    def forces(self, sigma, gamma=1.0):
+        sigma = self._dev(sigma)
+        F = self._f64(2 * self.n)
+        T = self._f64(self.n)
+        e = ctypes.c_double()
+        self._check(self.lib.yq_forces(self.h, _ptr(sigma), float(gamma), _ptr(F), _ptr(T),
+                                       ctypes.byref(e)))
+        return F.view(self.n, 2), T, e.value
+
+    def eval_potential(self, sigma, targets):
+        sigma = self._dev(sigma)
+        t = self._dev(targets).reshape(-1, 2)
+        tx, ty = t[:, 0].contiguous(), t[:, 1].contiguous()
+        u = self._f64(t.shape[0])
+        self._check(self.lib.yq_eval_potential(self.h, _ptr(sigma), t.shape[0], _ptr(tx), _ptr(ty),
+                                               _ptr(u)))
+        return u
+
+
+def bessel(kind, order, z, precision=YQ_FP64):
+    """Device special functions: kind 0 K0, 1 K1, 2 K_order, 3 I_order."""
+    torch = _torch()
+    lib = _lib.load()
+    z = torch.as_tensor(z, dtype=torch.float64, device="cuda").contiguous()
+    out = torch.empty_like(z)
+    torch.cuda.synchronize()
+    _lib.check(lib.yq_bessel(kind, order, precision, z.numel(), _ptr(z), _ptr(out)))
+    return out

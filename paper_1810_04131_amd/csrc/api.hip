@@ -1,0 +1,815 @@
+// The C ABI (include/yqbx.h): problem set-up, operator, GMRES solve with
+// optional mixed-precision refinement, surface gradient, forces, potential.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <numeric>
+
+#include "common.h"
+
+using namespace yq;
+
+struct yq_problem {
+  yq_params prm{};
+  hipStream_t stream = nullptr;
+  std::string err;
+
+  int n = 0;
+  int64_t N = 0;
+  double kappa = 0.0;
+  bool ready = false;
+  bool have_f = false;
+
+  std::vector<double> h_pc;  // [n*5]
+  DevBuf<double> pc, x, y, nx, ny, w, wnx, wny, panel_h, pcx, pcy, pr;
+  DevBuf<float> wnx32, wny32;
+  DevBuf<double> pot_partial;
+  DevBuf<int> nb_ptr, nb_idx, bad;
+  DevBuf<int> xrow, xpan;
+  int64_t x_total = 0;
+  DevBuf<double> xvals, xgvals;
+  DevBuf<double> W, WGx, WGy;
+  DevBuf<double> Lqbx, Lnear, Lpot, tab;
+  Consts consts{};
+  FarPlan fp{};
+  DevBuf<double> partial, gpartial;
+  DevBuf<float> partial32;
+  DevBuf<double> f;
+  // Krylov workspace
+  DevBuf<double> V, kw, kr, kd, kpart, kred;
+  DevBuf<double> gx, gy, en;
+
+  // per-phase timers
+  static constexpr int NPHASE = 6;
+  bool prof = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[NPHASE];
+  std::vector<hipEvent_t> pool;
+
+  hipEvent_t event() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e;
+    YQ_HIP(hipEventCreate(&e));
+    return e;
+  }
+  ~yq_problem() {
+    for (auto& v : ev)
+      for (auto& p : v) {
+        (void)hipEventDestroy(p.first);
+        (void)hipEventDestroy(p.second);
+      }
+    for (auto e : pool) (void)hipEventDestroy(e);
+  }
+
+  GeomView view() const {
+    GeomView g;
+    g.n = n;
+    g.P = prm.panels_per_particle;
+    g.N = N;
+    g.kappa = kappa;
+    g.pc = pc.p;
+    g.x = x.p;
+    g.y = y.p;
+    g.nx = nx.p;
+    g.ny = ny.p;
+    g.w = w.p;
+    g.wnx = wnx.p;
+    g.wny = wny.p;
+    g.panel_h = panel_h.p;
+    g.tab = tab.p;
+    return g;
+  }
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+// Brackets the launches issued in its scope with a pair of events when profiling is on.
+struct Timed {
+  yq_problem* pb;
+  int phase;
+  hipEvent_t a = nullptr;
+  Timed(yq_problem* p, int ph) : pb(p), phase(ph) {
+    if (pb->prof) {
+      a = pb->event();
+      YQ_HIP(hipEventRecord(a, pb->stream));
+    }
+  }
+  ~Timed() {
+    if (a) {
+      hipEvent_t b = pb->event();
+      (void)hipEventRecord(b, pb->stream);
+      pb->ev[phase].push_back({a, b});
+    }
+  }
+};
+
+int fail(yq_problem* pb, const Error& e) {
+  if (pb) pb->err = e.msg;
+  g_last_error = e.msg;
+  return e.code;
+}
+
+template <class F>
+int guarded(yq_problem* pb, F&& fn) {
+  try {
+    fn();
+    return YQ_OK;
+  } catch (const Error& e) {
+    return fail(pb, e);
+  } catch (const std::exception& e) {
+    return fail(pb, Error{YQ_EDEVICE, e.what()});
+  } catch (...) {
+    return fail(pb, Error{YQ_EDEVICE, "unknown error"});
+  }
+}
+
+void check_params(const yq_params& p) {
+  YQ_REQUIRE(p.qbx_order >= 1 && p.qbx_order <= MAXP, YQ_EINVAL, "qbx_order out of range 1..30");
+  YQ_REQUIRE(p.qbx_window >= 0 && p.qbx_window <= 8, YQ_EINVAL, "qbx_window out of range 0..8");
+  YQ_REQUIRE(p.panels_per_particle >= 2 * p.qbx_window + 1 && p.panels_per_particle <= 4096,
+             YQ_EINVAL, "panels_per_particle must be in 2*qbx_window+1..4096");
+  YQ_REQUIRE(p.qbx_oversample >= 1 && p.qbx_oversample <= MAXSUB, YQ_EINVAL,
+             "qbx_oversample out of range 1..16");
+  YQ_REQUIRE(p.near_oversample >= 1 && p.near_oversample <= MAXSUB, YQ_EINVAL,
+             "near_oversample out of range 1..16");
+  YQ_REQUIRE(p.pot_oversample >= 1 && p.pot_oversample <= MAXSUB, YQ_EINVAL,
+             "pot_oversample out of range 1..16");
+  YQ_REQUIRE(p.qbx_radius > 0.0 && p.qbx_radius < 1.0, YQ_EINVAL, "qbx_radius must be in (0, 1)");
+  YQ_REQUIRE(p.near_beta >= 0.0 && p.pot_beta >= 0.0, YQ_EINVAL, "near_beta, pot_beta >= 0");
+  YQ_REQUIRE(p.precision == YQ_FP64 || p.precision == YQ_MIXED, YQ_EINVAL, "bad precision");
+  YQ_REQUIRE(p.far_mode == YQ_FAR_DIRECT || p.far_mode == YQ_FAR_AUTO, YQ_EINVAL,
+             "far_mode: only YQ_FAR_DIRECT / YQ_FAR_AUTO are available in this build");
+  YQ_REQUIRE(p.tol > 0.0 && p.maxiter >= 1 && p.restart >= 1 && p.restart <= 200, YQ_EINVAL,
+             "tol > 0, maxiter >= 1, 1 <= restart <= 200");
+  YQ_REQUIRE(p.inner_tol > 0.0 && p.inner_tol < 1.0 && p.max_refine >= 1, YQ_EINVAL,
+             "inner_tol in (0, 1), max_refine >= 1");
+}
+
+void upload(DevBuf<double>& b, const std::vector<double>& h, hipStream_t s) {
+  b.alloc(h.size());
+  YQ_HIP(hipMemcpyAsync(b.p, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice, s));
+}
+
+void upload_i(DevBuf<int>& b, const std::vector<int>& h, hipStream_t s) {
+  b.alloc(std::max<size_t>(h.size(), 1));
+  if (!h.empty())
+    YQ_HIP(hipMemcpyAsync(b.p, h.data(), h.size() * sizeof(int), hipMemcpyHostToDevice, s));
+}
+
+std::vector<double> interp_for(const Consts& c, int nsub) {
+  std::vector<double> xi(nsub * Q), L(nsub * Q * Q);
+  sub_panel_coords(c.xg, Q, nsub, xi.data());
+  lagrange_matrix(c.xg, Q, xi.data(), nsub * Q, L.data());
+  return L;
+}
+
+// ---- operator ------------------------------------------------------------------------------
+
+void apply_op(yq_problem* pb, const double* sigma, double* out, int prec) {
+  GeomView g = pb->view();
+  const int win = pb->prm.qbx_window;
+  if (prec == YQ_MIXED) {
+    {
+      Timed t(pb, 1);
+      launch_far32(pb->x.p, pb->y.p, pb->wnx32.p, pb->wny32.p, sigma, pb->N, pb->kappa,
+                   pb->fp, pb->partial32.p, pb->stream);
+    }
+    Timed t(pb, 2);
+    launch_finish(g, win, pb->fp, nullptr, pb->partial32.p, pb->W.p, pb->xrow.p, pb->xpan.p,
+                  pb->xvals.p, sigma, out, pb->stream);
+  } else {
+    {
+      Timed t(pb, 0);
+      launch_far64(g, sigma, pb->fp, pb->partial.p, pb->stream);
+    }
+    Timed t(pb, 2);
+    launch_finish(g, win, pb->fp, pb->partial.p, nullptr, pb->W.p, pb->xrow.p, pb->xpan.p,
+                  pb->xvals.p, sigma, out, pb->stream);
+  }
+}
+
+// ---- GMRES -----------------------------------------------------------------------------------
+
+double dot_host(yq_problem* pb, const double* a, const double* b) {
+  const int nb = krylov_blocks(pb->N);
+  launch_multidot(a, 0, 1, b, pb->N, pb->kpart.p, nb, pb->stream);
+  launch_reduce(pb->kpart.p, 1, nb, pb->kred.p, pb->stream);
+  double v;
+  YQ_HIP(hipMemcpyAsync(&v, pb->kred.p, sizeof(double), hipMemcpyDeviceToHost, pb->stream));
+  YQ_HIP(hipStreamSynchronize(pb->stream));
+  return v;
+}
+
+struct GmresResult {
+  int iterations = 0;
+  int cycles = 0;
+  int matvecs = 0;
+  bool converged = false;
+  double rel = 0.0;  // residual estimate relative to ||b||
+};
+
+// Solves A x = b with restarted GMRES; x holds the initial guess (x_zero: 0).
+// The operator is applied with precision prec; Arnoldi is FP64 (CGS2).
+GmresResult gmres(yq_problem* pb, int prec, const double* b, double* x, bool x_zero, double rtol,
+                  int maxit) {
+  GmresResult R;
+  const int64_t N = pb->N;
+  const int m = pb->prm.restart;
+  const int nb = krylov_blocks(N);
+  hipStream_t s = pb->stream;
+  double* V = pb->V.p;
+  double* w = pb->kw.p;
+  double* r = pb->kr.p;
+
+  const double bnorm = std::sqrt(dot_host(pb, b, b));
+  if (bnorm == 0.0) {
+    YQ_HIP(hipMemsetAsync(x, 0, N * sizeof(double), s));
+    R.converged = true;
+    return R;
+  }
+  if (x_zero) YQ_HIP(hipMemsetAsync(x, 0, N * sizeof(double), s));
+
+  std::vector<double> H((m + 1) * m), cs(m), sn(m), gv(m + 1), hbuf(2 * (m + 1) + 1);
+  bool first = true;
+  while (true) {
+    // r = b - A x
+    if (first && x_zero) {
+      YQ_HIP(hipMemcpyAsync(r, b, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+    } else {
+      apply_op(pb, x, w, prec);
+      ++R.matvecs;
+      launch_axpby(-1.0, w, 1.0, b, r, N, s);
+    }
+    first = false;
+    const double beta = std::sqrt(dot_host(pb, r, r));
+    R.rel = beta / bnorm;
+    if (R.rel <= rtol) {
+      R.converged = true;
+      return R;
+    }
+    if (R.iterations >= maxit) return R;
+    ++R.cycles;
+    launch_axpby(1.0 / beta, r, 0.0, nullptr, V, N, s);
+    std::fill(gv.begin(), gv.end(), 0.0);
+    gv[0] = beta;
+    int j = 0;
+    bool done = false;
+    for (; j < m && R.iterations < maxit; ++j) {
+      double* vj = V + (int64_t)j * N;
+      double* vn = V + (int64_t)(j + 1) * N;
+      apply_op(pb, vj, w, prec);
+      ++R.matvecs;
+      // classical Gram-Schmidt, twice
+      launch_multidot(V, N, j + 1, w, N, pb->kpart.p, nb, s);
+      launch_reduce(pb->kpart.p, j + 1, nb, pb->kred.p, s);
+      launch_update(w, V, N, j + 1, pb->kred.p, -1.0, N, s);
+      launch_multidot(V, N, j + 1, w, N, pb->kpart.p, nb, s);
+      launch_reduce(pb->kpart.p, j + 1, nb, pb->kred.p + (j + 1), s);
+      launch_update(w, V, N, j + 1, pb->kred.p + (j + 1), -1.0, N, s);
+      launch_multidot(w, 0, 1, w, N, pb->kpart.p, nb, s);
+      launch_reduce(pb->kpart.p, 1, nb, pb->kred.p + 2 * (j + 1), s);
+      YQ_HIP(hipMemcpyAsync(hbuf.data(), pb->kred.p, (2 * (j + 1) + 1) * sizeof(double),
+                            hipMemcpyDeviceToHost, s));
+      YQ_HIP(hipStreamSynchronize(s));
+      ++R.iterations;
+      double* hc = &H[(size_t)j * (m + 1)];  // column j, rows 0..j+1
+      for (int i = 0; i <= j; ++i) hc[i] = hbuf[i] + hbuf[j + 1 + i];
+      const double hn = std::sqrt(std::max(hbuf[2 * (j + 1)], 0.0));
+      hc[j + 1] = hn;
+      if (hn > 0.0) launch_axpby(1.0 / hn, w, 0.0, nullptr, vn, N, s);
+      for (int i = 0; i < j; ++i) {
+        const double t = cs[i] * hc[i] + sn[i] * hc[i + 1];
+        hc[i + 1] = -sn[i] * hc[i] + cs[i] * hc[i + 1];
+        hc[i] = t;
+      }
+      const double den = std::hypot(hc[j], hc[j + 1]);
+      cs[j] = den > 0.0 ? hc[j] / den : 1.0;
+      sn[j] = den > 0.0 ? hc[j + 1] / den : 0.0;
+      hc[j] = den;
+      hc[j + 1] = 0.0;
+      gv[j + 1] = -sn[j] * gv[j];
+      gv[j] = cs[j] * gv[j];
+      R.rel = std::fabs(gv[j + 1]) / bnorm;
+      if (R.rel <= rtol || hn == 0.0) {
+        ++j;
+        done = true;
+        break;
+      }
+    }
+    // y = H^-1 g (upper triangular), x += V y
+    const int k = j;
+    std::vector<double> yv(k);
+    for (int i = k - 1; i >= 0; --i) {
+      double t = gv[i];
+      for (int c = i + 1; c < k; ++c) t -= H[(size_t)c * (m + 1) + i] * yv[c];
+      yv[i] = t / H[(size_t)i * (m + 1) + i];
+    }
+    if (k > 0) {
+      YQ_HIP(hipMemcpyAsync(pb->kred.p, yv.data(), k * sizeof(double), hipMemcpyHostToDevice, s));
+      launch_update(x, V, N, k, pb->kred.p, 1.0, N, s);
+    }
+    if (done) {
+      R.converged = true;
+      return R;
+    }
+    if (R.iterations >= maxit) return R;
+  }
+}
+
+void ensure_krylov(yq_problem* pb) {
+  const int64_t N = pb->N;
+  const int m = pb->prm.restart;
+  pb->V.reserve((size_t)(m + 1) * N);
+  pb->kw.reserve(N);
+  pb->kr.reserve(N);
+  pb->kd.reserve(N);
+  pb->kpart.reserve((size_t)krylov_blocks(N) * (m + 1));
+  pb->kred.reserve(2 * (m + 1) + 8);
+}
+
+void require_ready(const yq_problem* pb) {
+  YQ_REQUIRE(pb != nullptr, YQ_EINVAL, "null problem");
+  YQ_REQUIRE(pb->ready, YQ_ESTATE, "yq_set_particles has not been called");
+}
+
+}  // namespace
+
+// =============================================================================================
+extern "C" {
+
+void yq_default_params(yq_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->panels_per_particle = 32;
+  p->qbx_order = 10;
+  p->qbx_window = 2;
+  p->qbx_oversample = 4;
+  p->qbx_radius = 0.25;
+  p->near_beta = 0.5;
+  p->near_oversample = 4;
+  p->pot_oversample = 8;
+  p->pot_beta = 0.5;
+  p->precision = YQ_FP64;
+  p->far_mode = YQ_FAR_DIRECT;
+  p->fmm_order = 20;
+  p->fmm_leaf_max = 64;
+  p->tol = 1e-10;
+  p->maxiter = 200;
+  p->restart = 100;
+  p->inner_tol = 1e-6;
+  p->max_refine = 8;
+}
+
+const char* yq_error_string(int status) {
+  switch (status) {
+    case YQ_OK: return "ok";
+    case YQ_EINVAL: return "invalid argument";
+    case YQ_EGEOM: return "geometry rejected";
+    case YQ_ENOCONV: return "GMRES did not converge";
+    case YQ_ENOMEM: return "device memory allocation failed";
+    case YQ_EDEVICE: return "HIP runtime error";
+    case YQ_ESTATE: return "call out of order";
+    case YQ_EADMIT: return "request refused by admission";
+    default: return "unknown status";
+  }
+}
+
+const char* yq_last_error(const yq_problem* pb) {
+  return pb ? pb->err.c_str() : g_last_error.c_str();
+}
+
+int yq_create(const yq_params* params, yq_problem** out) {
+  return guarded(nullptr, [&] {
+    YQ_REQUIRE(params && out, YQ_EINVAL, "null argument");
+    check_params(*params);
+    auto pb = std::make_unique<yq_problem>();
+    pb->prm = *params;
+    gauss_legendre16(pb->consts.xg, pb->consts.wg);
+    std::vector<double> t(T_SIZE_HOST);
+    fill_tab64(t.data());
+    upload(pb->tab, t, nullptr);
+    YQ_HIP(hipStreamSynchronize(nullptr));
+    *out = pb.release();
+  });
+}
+
+void yq_destroy(yq_problem* pb) {
+  if (!pb) return;
+  (void)hipStreamSynchronize(pb->stream);
+  delete pb;
+}
+
+int yq_set_stream(yq_problem* pb, void* stream) {
+  return guarded(pb, [&] {
+    YQ_REQUIRE(pb, YQ_EINVAL, "null problem");
+    pb->stream = (hipStream_t)stream;
+  });
+}
+
+int yq_set_particles(yq_problem* pb, int32_t n, const double* center_xy, const double* angle,
+                     const double* semi_axes, double kappa) {
+  return guarded(pb, [&] {
+    YQ_REQUIRE(pb && center_xy && angle && semi_axes, YQ_EINVAL, "null argument");
+    YQ_REQUIRE(n >= 1, YQ_EINVAL, "need at least one particle");
+    YQ_REQUIRE(std::isfinite(kappa) && kappa > 0.0, YQ_EINVAL, "kappa must be finite and > 0");
+    const int P = pb->prm.panels_per_particle;
+    const int64_t N = (int64_t)n * P * Q;
+    YQ_REQUIRE(N < (int64_t)INT32_MAX, YQ_EINVAL, "too many nodes for one problem");
+    double amax = 0.0;
+    pb->h_pc.assign((size_t)n * 5, 0.0);
+    for (int i = 0; i < n; ++i) {
+      const double cx = center_xy[2 * i], cy = center_xy[2 * i + 1], th = angle[i];
+      const double A = semi_axes[2 * i], B = semi_axes[2 * i + 1];
+      YQ_REQUIRE(std::isfinite(cx) && std::isfinite(cy) && std::isfinite(th) &&
+                     std::isfinite(A) && std::isfinite(B),
+                 YQ_EINVAL, "non-finite particle data");
+      YQ_REQUIRE(B > 0.0 && A >= B, YQ_EINVAL, "semi-axes must satisfy A >= B > 0");
+      double* q = &pb->h_pc[5 * (size_t)i];
+      q[0] = cx;
+      q[1] = cy;
+      q[2] = th;
+      q[3] = A;
+      q[4] = B;
+      amax = std::max(amax, A);
+    }
+    pb->ready = false;
+    pb->have_f = false;
+    pb->n = n;
+    pb->N = N;
+    pb->kappa = kappa;
+    hipStream_t s = pb->stream;
+
+    // particle neighbour lists (host): every particle whose ellipse could hold
+    // a near panel of, or overlap, particle p; p itself is included.
+    const double margin = std::max(pb->prm.near_beta, pb->prm.pot_beta) * 2.0 * PI * amax / P *
+                              1.01 + 1e-9;
+    std::vector<int> nbp(n + 1, 0), nbi;
+    for (int p = 0; p < n; ++p) {
+      const double* a = &pb->h_pc[5 * (size_t)p];
+      for (int q = 0; q < n; ++q) {
+        const double* b = &pb->h_pc[5 * (size_t)q];
+        const double d = std::hypot(a[0] - b[0], a[1] - b[1]);
+        if (q == p || d < a[3] + b[3] + margin) nbi.push_back(q);
+      }
+      nbp[p + 1] = (int)nbi.size();
+    }
+    upload(pb->pc, pb->h_pc, s);
+    upload_i(pb->nb_ptr, nbp, s);
+    upload_i(pb->nb_idx, nbi, s);
+
+    // a1: nodes, normals, weights; panel arclengths and bounding circles
+    pb->x.alloc(N);
+    pb->y.alloc(N);
+    pb->nx.alloc(N);
+    pb->ny.alloc(N);
+    pb->w.alloc(N);
+    pb->wnx.alloc(N);
+    pb->wny.alloc(N);
+    pb->panel_h.alloc((size_t)n * P);
+    pb->pcx.alloc((size_t)n * P);
+    pb->pcy.alloc((size_t)n * P);
+    pb->pr.alloc((size_t)n * P);
+    GeomView g = pb->view();
+    launch_geometry(g, pb->consts, pb->x.p, pb->y.p, pb->nx.p, pb->ny.p, pb->w.p, pb->wnx.p,
+                    pb->wny.p, s);
+    launch_panel_stats(g, pb->panel_h.p, pb->pcx.p, pb->pcy.p, pb->pr.p, s);
+
+    // geometry check
+    pb->bad.alloc(1);
+    YQ_HIP(hipMemsetAsync(pb->bad.p, 0, sizeof(int), s));
+    launch_geom_check(g, pb->nb_ptr.p, pb->nb_idx.p, pb->bad.p, s);
+    int bad = 0;
+    YQ_HIP(hipMemcpyAsync(&bad, pb->bad.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    YQ_HIP(hipStreamSynchronize(s));
+    YQ_REQUIRE(bad == 0, YQ_EGEOM, "a node of one particle lies inside another particle");
+
+    // a3: extra near panels (count, prefix sum, fill)
+    pb->xrow.alloc(N + 1);
+    DevBuf<int> cnt;
+    cnt.alloc(N);
+    launch_near_count(g, pb->prm.qbx_window, pb->prm.near_beta, pb->nb_ptr.p, pb->nb_idx.p,
+                      pb->pcx.p, pb->pcy.p, pb->pr.p, cnt.p, nullptr, nullptr, s);
+    std::vector<int> hc(N), hrow(N + 1, 0);
+    YQ_HIP(hipMemcpyAsync(hc.data(), cnt.p, N * sizeof(int), hipMemcpyDeviceToHost, s));
+    YQ_HIP(hipStreamSynchronize(s));
+    for (int64_t i = 0; i < N; ++i) hrow[i + 1] = hrow[i] + hc[i];
+    pb->x_total = hrow[N];
+    YQ_HIP(hipMemcpyAsync(pb->xrow.p, hrow.data(), (N + 1) * sizeof(int), hipMemcpyHostToDevice, s));
+    pb->xpan.alloc(std::max<int64_t>(pb->x_total, 1));
+    pb->xvals.alloc(std::max<int64_t>(pb->x_total, 1) * Q);
+    pb->xgvals.alloc(std::max<int64_t>(pb->x_total, 1) * 2 * Q);
+    if (pb->x_total > 0)
+      launch_near_count(g, pb->prm.qbx_window, pb->prm.near_beta, pb->nb_ptr.p, pb->nb_idx.p,
+                        pb->pcx.p, pb->pcy.p, pb->pr.p, nullptr, pb->xpan.p, pb->xrow.p, s);
+
+    // a4: QBX correction (window) and oversampled rows (extra near panels)
+    upload(pb->Lqbx, interp_for(pb->consts, pb->prm.qbx_oversample), s);
+    upload(pb->Lnear, interp_for(pb->consts, pb->prm.near_oversample), s);
+    upload(pb->Lpot, interp_for(pb->consts, pb->prm.pot_oversample), s);
+    const size_t wsz = (size_t)(2 * pb->prm.qbx_window + 1) * Q * N;
+    pb->W.alloc(wsz);
+    pb->WGx.alloc(wsz);
+    pb->WGy.alloc(wsz);
+    {
+      Timed t(pb, 4);
+      launch_qbx_build(g, pb->consts, pb->prm.qbx_order, pb->prm.qbx_window,
+                       pb->prm.qbx_oversample, pb->prm.qbx_radius, pb->Lqbx.p, pb->W.p, pb->WGx.p,
+                       pb->WGy.p, s);
+    }
+    if (pb->x_total > 0)
+      launch_near_rows(g, pb->consts, pb->prm.near_oversample, pb->Lnear.p, pb->xrow.p,
+                       pb->xpan.p, pb->xvals.p, pb->xgvals.p, s);
+
+    // FP32 copies for the mixed-precision far field
+    pb->wnx32.alloc(N);
+    pb->wny32.alloc(N);
+    launch_to_f32(pb->wnx.p, pb->wnx32.p, N, s);
+    launch_to_f32(pb->wny.p, pb->wny32.p, N, s);
+
+    pb->fp = far_plan(N, N, 256);
+    pb->partial.alloc((size_t)pb->fp.chunks * N);
+    pb->partial32.alloc((size_t)pb->fp.chunks * N);
+    pb->gpartial.alloc((size_t)pb->fp.chunks * 2 * N);
+    pb->f.alloc(N);
+    pb->gx.alloc(N);
+    pb->gy.alloc(N);
+    pb->en.alloc(n);
+    ensure_krylov(pb);
+    YQ_HIP(hipStreamSynchronize(s));
+    pb->ready = true;
+  });
+}
+
+int yq_num_nodes(const yq_problem* pb, int64_t* N) {
+  if (!pb || !N) return YQ_EINVAL;
+  *N = pb->N;
+  return YQ_OK;
+}
+
+int yq_num_particles(const yq_problem* pb, int32_t* n) {
+  if (!pb || !n) return YQ_EINVAL;
+  *n = pb->n;
+  return YQ_OK;
+}
+
+int yq_get_nodes(const yq_problem* cpb, double* x, double* y, double* nx, double* ny, double* w) {
+  yq_problem* pb = const_cast<yq_problem*>(cpb);
+  return guarded(pb, [&] {
+    require_ready(pb);
+    const size_t b = pb->N * sizeof(double);
+    hipStream_t s = pb->stream;
+    if (x) YQ_HIP(hipMemcpyAsync(x, pb->x.p, b, hipMemcpyDeviceToDevice, s));
+    if (y) YQ_HIP(hipMemcpyAsync(y, pb->y.p, b, hipMemcpyDeviceToDevice, s));
+    if (nx) YQ_HIP(hipMemcpyAsync(nx, pb->nx.p, b, hipMemcpyDeviceToDevice, s));
+    if (ny) YQ_HIP(hipMemcpyAsync(ny, pb->ny.p, b, hipMemcpyDeviceToDevice, s));
+    if (w) YQ_HIP(hipMemcpyAsync(w, pb->w.p, b, hipMemcpyDeviceToDevice, s));
+    YQ_HIP(hipStreamSynchronize(s));
+  });
+}
+
+int yq_near_count(const yq_problem* pb, int64_t* total) {
+  if (!pb || !total) return YQ_EINVAL;
+  if (!pb->ready) return YQ_ESTATE;
+  *total = pb->x_total;
+  return YQ_OK;
+}
+
+int yq_get_near(const yq_problem* cpb, int32_t* row_ptr, int32_t* panels) {
+  yq_problem* pb = const_cast<yq_problem*>(cpb);
+  return guarded(pb, [&] {
+    require_ready(pb);
+    YQ_REQUIRE(row_ptr, YQ_EINVAL, "null row_ptr");
+    hipStream_t s = pb->stream;
+    YQ_HIP(hipMemcpyAsync(row_ptr, pb->xrow.p, (pb->N + 1) * sizeof(int), hipMemcpyDeviceToDevice, s));
+    if (pb->x_total > 0) {
+      YQ_REQUIRE(panels, YQ_EINVAL, "null panels");
+      YQ_HIP(hipMemcpyAsync(panels, pb->xpan.p, pb->x_total * sizeof(int), hipMemcpyDeviceToDevice, s));
+    }
+    YQ_HIP(hipStreamSynchronize(s));
+  });
+}
+
+int yq_boundary_label(yq_problem* pb, int32_t kind, double a, double b, double* f) {
+  return guarded(pb, [&] {
+    require_ready(pb);
+    YQ_REQUIRE(f, YQ_EINVAL, "null f");
+    YQ_REQUIRE(kind == YQ_LABEL_ARC || kind == YQ_LABEL_JANUS, YQ_EINVAL, "unknown label kind");
+    YQ_REQUIRE(kind != YQ_LABEL_ARC || b > 0.0, YQ_EINVAL, "arc edge width must be > 0");
+    launch_label(pb->view(), kind, a, b, f, pb->stream);
+    YQ_HIP(hipStreamSynchronize(pb->stream));
+  });
+}
+
+int yq_set_boundary_data(yq_problem* pb, const double* f) {
+  return guarded(pb, [&] {
+    require_ready(pb);
+    YQ_REQUIRE(f, YQ_EINVAL, "null f");
+    YQ_HIP(hipMemcpyAsync(pb->f.p, f, pb->N * sizeof(double), hipMemcpyDeviceToDevice, pb->stream));
+    pb->have_f = true;
+  });
+}
+
+int yq_apply_far(yq_problem* pb, const double* sigma, double* out, int32_t precision) {
+  return guarded(pb, [&] {
+    require_ready(pb);
+    YQ_REQUIRE(sigma && out, YQ_EINVAL, "null argument");
+    YQ_REQUIRE(precision == YQ_FP64 || precision == YQ_MIXED, YQ_EINVAL, "bad precision");
+    GeomView g = pb->view();
+    // far field with a zero near correction: reuse finish with window 0 rows skipped
+    if (precision == YQ_MIXED)
+      launch_far32(pb->x.p, pb->y.p, pb->wnx32.p, pb->wny32.p, sigma, pb->N, pb->kappa,
+                   pb->fp, pb->partial32.p, pb->stream);
+    else
+      launch_far64(g, sigma, pb->fp, pb->partial.p, pb->stream);
+    launch_finish(g, -1, pb->fp, precision == YQ_MIXED ? nullptr : pb->partial.p,
+                  precision == YQ_MIXED ? pb->partial32.p : nullptr, pb->W.p, pb->xrow.p,
+                  pb->xpan.p, nullptr, sigma, out, pb->stream);
+  });
+}
+
+int yq_apply_operator(yq_problem* pb, const double* sigma, double* out, int32_t precision) {
+  return guarded(pb, [&] {
+    require_ready(pb);
+    YQ_REQUIRE(sigma && out && sigma != out, YQ_EINVAL, "null or aliased argument");
+    YQ_REQUIRE(precision == YQ_FP64 || precision == YQ_MIXED, YQ_EINVAL, "bad precision");
+    apply_op(pb, sigma, out, precision);
+  });
+}
+
+int yq_solve(yq_problem* pb, const double* sigma0, double* sigma, yq_solve_info* info) {
+  int status = YQ_OK;
+  int rc = guarded(pb, [&] {
+    require_ready(pb);
+    YQ_REQUIRE(sigma, YQ_EINVAL, "null sigma");
+    YQ_REQUIRE(pb->have_f, YQ_ESTATE, "boundary data not set");
+    auto t0 = std::chrono::steady_clock::now();
+    hipStream_t s = pb->stream;
+    const int64_t N = pb->N;
+    yq_solve_info inf{};
+    if (sigma0 && sigma0 != sigma)
+      YQ_HIP(hipMemcpyAsync(sigma, sigma0, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+    bool zero = sigma0 == nullptr;
+    bool conv = false;
+    double* r = pb->kd.p;  // refinement residual
+    if (pb->prm.precision == YQ_FP64) {
+      GmresResult R = gmres(pb, YQ_FP64, pb->f.p, sigma, zero, pb->prm.tol, pb->prm.maxiter);
+      inf.iterations = R.iterations;
+      inf.outer_steps = R.cycles;
+      inf.matvecs_fp64 = R.matvecs;
+      conv = R.converged;
+    } else {
+      // mixed precision: FP64 residual, FP32-far-field inner GMRES, sigma += delta
+      if (zero) YQ_HIP(hipMemsetAsync(sigma, 0, N * sizeof(double), s));
+      DevBuf<double> delta;
+      delta.alloc(N);
+      const double fnorm = std::sqrt(dot_host(pb, pb->f.p, pb->f.p));
+      int budget = pb->prm.maxiter;
+      for (int outer = 0; outer < pb->prm.max_refine; ++outer) {
+        double rel;
+        if (outer == 0 && zero) {
+          YQ_HIP(hipMemcpyAsync(r, pb->f.p, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+          rel = 1.0;
+        } else {
+          apply_op(pb, sigma, pb->kw.p, YQ_FP64);
+          ++inf.matvecs_fp64;
+          launch_axpby(-1.0, pb->kw.p, 1.0, pb->f.p, r, N, s);
+          rel = fnorm > 0.0 ? std::sqrt(dot_host(pb, r, r)) / fnorm : 0.0;
+        }
+        if (rel <= pb->prm.tol) {
+          conv = true;
+          break;
+        }
+        if (budget <= 0) break;
+        ++inf.outer_steps;
+        const double itol = std::max(pb->prm.inner_tol, 0.5 * pb->prm.tol / std::max(rel, 1e-300));
+        GmresResult R = gmres(pb, YQ_MIXED, r, delta.p, true, std::min(itol, 0.5), budget);
+        inf.iterations += R.iterations;
+        inf.matvecs_fp32 += R.matvecs;
+        budget -= R.iterations;
+        launch_axpby(1.0, delta.p, 1.0, sigma, sigma, N, s);
+      }
+    }
+    // true FP64 residual
+    apply_op(pb, sigma, pb->kw.p, YQ_FP64);
+    ++inf.matvecs_fp64;
+    launch_axpby(-1.0, pb->kw.p, 1.0, pb->f.p, r, N, s);
+    const double fn = std::sqrt(dot_host(pb, pb->f.p, pb->f.p));
+    inf.residual = fn > 0.0 ? std::sqrt(dot_host(pb, r, r)) / fn : 0.0;
+    if (pb->prm.precision == YQ_MIXED) conv = inf.residual <= pb->prm.tol;
+    inf.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (info) *info = inf;
+    if (!conv) status = YQ_ENOCONV;
+  });
+  if (rc != YQ_OK) return rc;
+  if (status != YQ_OK && pb) pb->err = "GMRES did not reach the tolerance";
+  return status;
+}
+
+int yq_surface_gradient(yq_problem* pb, const double* sigma, double* gx, double* gy) {
+  return guarded(pb, [&] {
+    require_ready(pb);
+    YQ_REQUIRE(sigma && gx && gy, YQ_EINVAL, "null argument");
+    GeomView g = pb->view();
+    {
+      Timed t(pb, 3);
+      launch_far_grad64(g, sigma, pb->fp, pb->gpartial.p, pb->stream);
+    }
+    launch_finish_grad(g, pb->prm.qbx_window, pb->fp, pb->gpartial.p, pb->WGx.p, pb->WGy.p,
+                       pb->xrow.p, pb->xpan.p, pb->xgvals.p, sigma, gx, gy, pb->stream);
+  });
+}
+
+int yq_forces(yq_problem* pb, const double* sigma, double gamma, double* force, double* torque,
+              double* energy) {
+  return guarded(pb, [&] {
+    require_ready(pb);
+    YQ_REQUIRE(sigma && force && torque, YQ_EINVAL, "null argument");
+    YQ_REQUIRE(pb->have_f, YQ_ESTATE, "boundary data not set");
+    GeomView g = pb->view();
+    {
+      Timed t(pb, 3);
+      launch_far_grad64(g, sigma, pb->fp, pb->gpartial.p, pb->stream);
+    }
+    launch_finish_grad(g, pb->prm.qbx_window, pb->fp, pb->gpartial.p, pb->WGx.p, pb->WGy.p,
+                       pb->xrow.p, pb->xpan.p, pb->xgvals.p, sigma, pb->gx.p, pb->gy.p, pb->stream);
+    launch_forces(g, pb->f.p, pb->gx.p, pb->gy.p, gamma, force, torque, pb->en.p, pb->stream);
+    std::vector<double> e(pb->n);
+    YQ_HIP(hipMemcpyAsync(e.data(), pb->en.p, pb->n * sizeof(double), hipMemcpyDeviceToHost,
+                          pb->stream));
+    YQ_HIP(hipStreamSynchronize(pb->stream));
+    if (energy) {
+      double t = 0.0;
+      for (double v : e) t += v;
+      *energy = t;
+    }
+  });
+}
+
+int yq_eval_potential(yq_problem* pb, const double* sigma, int64_t M, const double* tx,
+                      const double* ty, double* u) {
+  return guarded(pb, [&] {
+    require_ready(pb);
+    YQ_REQUIRE(M >= 0, YQ_EINVAL, "M < 0");
+    if (M == 0) return;
+    YQ_REQUIRE(sigma && tx && ty && u, YQ_EINVAL, "null argument");
+    PotPlan pp = pot_plan(M, (int64_t)pb->n * pb->prm.panels_per_particle);
+    pb->pot_partial.reserve((size_t)pp.chunks * M);
+    launch_potential(pb->view(), pb->consts, pb->prm.pot_oversample, pb->Lpot.p, pb->prm.pot_beta,
+                     sigma, M, tx, ty, pp, pb->pot_partial.p, u, pb->stream);
+  });
+}
+
+int yq_profile_enable(yq_problem* pb, int32_t enable) {
+  return guarded(pb, [&] {
+    YQ_REQUIRE(pb, YQ_EINVAL, "null problem");
+    pb->prof = enable != 0;
+  });
+}
+
+int yq_profile_read(yq_problem* pb, int32_t phase, int64_t* launches, double* total_ms,
+                    int32_t reset) {
+  return guarded(pb, [&] {
+    YQ_REQUIRE(pb && launches && total_ms, YQ_EINVAL, "null argument");
+    YQ_REQUIRE(phase >= 0 && phase < yq_problem::NPHASE, YQ_EINVAL, "bad phase");
+    YQ_HIP(hipStreamSynchronize(pb->stream));
+    double tot = 0.0;
+    for (auto& p : pb->ev[phase]) {
+      float ms = 0.0f;
+      YQ_HIP(hipEventElapsedTime(&ms, p.first, p.second));
+      tot += ms;
+    }
+    *launches = (int64_t)pb->ev[phase].size();
+    *total_ms = tot;
+    if (reset) {
+      for (auto& p : pb->ev[phase]) {
+        pb->pool.push_back(p.first);
+        pb->pool.push_back(p.second);
+      }
+      pb->ev[phase].clear();
+    }
+  });
+}
+
+int yq_bessel(int32_t kind, int32_t order, int32_t precision, int64_t n, const double* z,
+              double* out) {
+  return guarded(nullptr, [&] {
+    YQ_REQUIRE(kind >= 0 && kind <= 3, YQ_EINVAL, "kind must be 0..3");
+    YQ_REQUIRE(order >= 0 && order <= MAXP + 1, YQ_EINVAL, "order out of range");
+    YQ_REQUIRE(n >= 0 && (n == 0 || (z && out)), YQ_EINVAL, "null argument");
+    std::vector<double> t(T_SIZE_HOST);
+    fill_tab64(t.data());
+    DevBuf<double> tab;
+    upload(tab, t, nullptr);
+    launch_bessel(kind, order, precision, n, z, out, tab.p, nullptr);
+    YQ_HIP(hipStreamSynchronize(nullptr));
+  });
+}
+
+}  // extern "C"

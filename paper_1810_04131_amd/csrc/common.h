@@ -1,0 +1,171 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "yqbx.h"
+
+namespace yq {
+
+constexpr int Q = 16;            // Gauss-Legendre nodes per panel
+constexpr int MAXP = 30;         // largest QBX order
+constexpr int MAXSUB = 16;       // largest oversampling factor
+constexpr double PI = 3.14159265358979323846264338327950288;
+constexpr int T_SIZE_HOST = 104;  // doubles in the FP64 coefficient table (bessel.h T_SIZE)
+
+struct Error {
+  int code;
+  std::string msg;
+};
+
+#define YQ_HIP(x)                                                                          \
+  do {                                                                                     \
+    hipError_t e_ = (x);                                                                   \
+    if (e_ != hipSuccess)                                                                  \
+      throw ::yq::Error{YQ_EDEVICE, std::string(#x) + ": " + hipGetErrorString(e_)};        \
+  } while (0)
+
+#define YQ_REQUIRE(cond, code, msg)                                                        \
+  do {                                                                                     \
+    if (!(cond)) throw ::yq::Error{(code), (msg)};                                         \
+  } while (0)
+
+// Owning device buffer (hipMalloc / hipFree).
+template <class T>
+struct DevBuf {
+  T* p = nullptr;
+  size_t n = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  void alloc(size_t count) {
+    if (count == n && p) return;
+    release();
+    if (count == 0) return;
+    hipError_t e = hipMalloc(&p, count * sizeof(T));
+    if (e != hipSuccess) {
+      p = nullptr;
+      throw Error{YQ_ENOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed"};
+    }
+    n = count;
+  }
+  // grows, never shrinks
+  void reserve(size_t count) {
+    if (count > n) alloc(count);
+  }
+  size_t bytes() const { return n * sizeof(T); }
+};
+
+// Geometry of one problem as the kernels see it (all device pointers).
+struct GeomView {
+  int n;                 // particles
+  int P;                 // panels per particle
+  int64_t N;             // nodes
+  double kappa;
+  const double* pc;      // particles: [n*5] (cx, cy, angle, A, B)
+  const double* x;       // nodes [N]
+  const double* y;
+  const double* nx;
+  const double* ny;
+  const double* w;
+  const double* wnx;     // w * nx
+  const double* wny;     // w * ny
+  const double* panel_h; // [n*P]
+  const double* tab;     // FP64 special-function coefficients (bessel.h, T_SIZE doubles)
+};
+
+// Discretisation constants, passed to kernels by value.
+struct Consts {
+  double xg[Q];                 // Gauss-Legendre nodes on [-1, 1], ascending
+  double wg[Q];                 // weights
+};
+
+// ---------------------------------------------------------------------------------------
+// Host launchers (implemented in the .hip files)
+// ---------------------------------------------------------------------------------------
+
+// gauss.cpp-like host helpers (geometry.hip)
+void gauss_legendre16(double* x, double* w);
+void lagrange_matrix(const double* src, int q, const double* dst, int nd, double* L);
+void sub_panel_coords(const double* xg, int q, int nsub, double* xi);
+
+void launch_geometry(const GeomView& g, const Consts& c, double* x, double* y, double* nx, double* ny, double* w,
+                     double* wnx, double* wny, hipStream_t s);
+void launch_panel_stats(const GeomView& g, double* panel_h, double* pcx, double* pcy, double* pr,
+                        hipStream_t s);
+void launch_to_f32(const double* in, float* out, int64_t n, hipStream_t s);
+void launch_label(const GeomView& g, int kind, double a, double b, double* f, hipStream_t s);
+void launch_geom_check(const GeomView& g, const int* nb_ptr, const int* nb_idx, int* bad,
+                       hipStream_t s);
+void launch_near_count(const GeomView& g, int win, double beta, const int* nb_ptr,
+                       const int* nb_idx, const double* pcx, const double* pcy, const double* pr,
+                       int* count, int* list, const int* offs, hipStream_t s);
+
+void launch_qbx_build(const GeomView& g, const Consts& c, int p, int win, int nsub, double radius,
+                      const double* L, double* W, double* WGx, double* WGy, hipStream_t s);
+void launch_near_rows(const GeomView& g, const Consts& c, int nsub, const double* L,
+                      const int* row_ptr, const int* panels, double* vals, double* gvals,
+                      hipStream_t s);
+
+struct FarPlan {
+  int tblocks;   // target blocks
+  int chunks;    // source chunks
+  int chunk;     // sources per chunk (multiple of the block size)
+};
+FarPlan far_plan(int64_t nt, int64_t ns, int block);
+void launch_far64(const GeomView& g, const double* sigma, const FarPlan& fp, double* partial,
+                  hipStream_t s);
+void launch_far32(const double* x, const double* y, const float* wnx, const float* wny,
+                  const double* sigma, int64_t N, double kappa, const FarPlan& fp, float* partial,
+                  hipStream_t s);
+void launch_finish(const GeomView& g, int win, const FarPlan& fp, const double* partial64,
+                   const float* partial32, const double* W, const int* xrow, const int* xpan,
+                   const double* xvals, const double* sigma, double* out, hipStream_t s);
+void launch_far_grad64(const GeomView& g, const double* sigma, const FarPlan& fp, double* partial,
+                       hipStream_t s);
+void launch_finish_grad(const GeomView& g, int win, const FarPlan& fp, const double* partial,
+                        const double* WGx, const double* WGy, const int* xrow, const int* xpan,
+                        const double* xgvals, const double* sigma, double* gx, double* gy,
+                        hipStream_t s);
+
+// Krylov helpers (krylov.hip)
+int krylov_blocks(int64_t n);
+void launch_multidot(const double* V, int64_t ld, int k, const double* w, int64_t n, double* partial,
+                     int nb, hipStream_t s);
+void launch_reduce(const double* partial, int k, int nb, double* out, hipStream_t s);
+void launch_update(double* w, const double* V, int64_t ld, int k, const double* h, double alpha,
+                   int64_t n, hipStream_t s);
+void launch_axpby(double a, const double* x, double b, const double* y, double* out, int64_t n,
+                  hipStream_t s);
+void launch_scale(const double* x, const double* inv, double* out, int64_t n, hipStream_t s);
+
+// post-processing (post.hip)
+void launch_forces(const GeomView& g, const double* f, const double* gx, const double* gy,
+                   double gamma, double* force, double* torque, double* energy_part,
+                   hipStream_t s);
+struct PotPlan {
+  int tblocks;   // target blocks of 64
+  int chunks;    // panel chunks
+  int per;       // panels per chunk
+};
+PotPlan pot_plan(int64_t M, int64_t npan);
+void launch_potential(const GeomView& g, const Consts& c, int nsub, const double* L, double beta,
+                      const double* sigma, int64_t M, const double* tx, const double* ty,
+                      const PotPlan& pp, double* partial, double* u, hipStream_t s);
+
+// special functions (bessel_test.hip)
+void launch_bessel(int kind, int order, int prec, int64_t n, const double* z, double* out,
+                   const double* tab, hipStream_t s);
+void fill_tab64(double* host_tab);   // writes the T_SIZE FP64 coefficients
+
+}  // namespace yq

@@ -1,0 +1,279 @@
+// Steps a5 (tiled direct far field) and a6 (near-correction apply).
+//
+// Far field: out_i = (kappa^2/2pi) sum_{j != i} [K1(z)/z] ((x_i - y_j) . q_j),
+// z = kappa |x_i - y_j|, q_j = w_j sigma_j nu_j -- the 16-point Nystrom rule of
+// the double layer dG/dnu_y = (kappa/2pi) K1(kappa r) (x-y).nu / r for every
+// pair (section 4, eq. double-layer-def; section 5).
+//
+// Mapping: one target per lane, 256-lane blocks; the source range is split
+// into chunks (grid.y) so that a launch has enough blocks to fill all compute
+// units; each block stages 256-source tiles (x, y, qx, qy) through LDS, and
+// every lane reads the same source at the same time (LDS broadcast).  Chunk
+// partial sums go to partial[chunk * N + i]; the finish kernel adds them in a
+// fixed order (deterministic), scales, and applies the near correction.
+#include "bessel.h"
+#include "common.h"
+
+namespace yq {
+
+constexpr int FAR_BS = 256;
+
+FarPlan far_plan(int64_t nt, int64_t ns, int block) {
+  FarPlan fp;
+  fp.tblocks = (int)((nt + block - 1) / block);
+  const int want = 4096;  // >= 16 blocks per compute unit
+  int64_t src_tiles = (ns + block - 1) / block;
+  int64_t chunks = (want + fp.tblocks - 1) / fp.tblocks;
+  if (chunks > src_tiles) chunks = src_tiles;
+  if (chunks < 1) chunks = 1;
+  int64_t tiles_per = (src_tiles + chunks - 1) / chunks;
+  fp.chunk = (int)(tiles_per * block);
+  fp.chunks = (int)((ns + fp.chunk - 1) / fp.chunk);
+  if (fp.chunks < 1) fp.chunks = 1;
+  return fp;
+}
+
+__global__ __launch_bounds__(FAR_BS) void far64_kernel(GeomView g, const double* __restrict__ sigma,
+                                                       int chunk, double* __restrict__ partial) {
+  __shared__ double2 sxy[FAR_BS];
+  __shared__ double2 sq[FAR_BS];
+  const int64_t N = g.N;
+  const int64_t i = blockIdx.x * (int64_t)FAR_BS + threadIdx.x;
+  const double xi = i < N ? g.x[i] : 0.0;
+  const double yi = i < N ? g.y[i] : 0.0;
+  const double kap2 = g.kappa * g.kappa;
+  const int64_t j0 = (int64_t)blockIdx.y * chunk;
+  const int64_t j1 = min(N, j0 + chunk);
+  double acc = 0.0;
+  for (int64_t jb = j0; jb < j1; jb += FAR_BS) {
+    const int64_t j = jb + threadIdx.x;
+    __syncthreads();
+    if (j < j1) {
+      const double s = sigma[j];
+      sxy[threadIdx.x] = make_double2(g.x[j], g.y[j]);
+      sq[threadIdx.x] = make_double2(g.wnx[j] * s, g.wny[j] * s);
+    }
+    __syncthreads();
+    const int nb = (int)min((int64_t)FAR_BS, j1 - jb);
+    for (int k = 0; k < nb; ++k) {
+      const double2 p = sxy[k];
+      const double2 q = sq[k];
+      const double dx = xi - p.x, dy = yi - p.y;
+      const double r2 = fma(dx, dx, dy * dy);
+      const double v = k1z_64(kap2 * r2, g.tab) * fma(dx, q.x, dy * q.y);
+      acc += r2 > 0.0 ? v : 0.0;
+    }
+  }
+  if (i < N) partial[(int64_t)blockIdx.y * N + i] = acc;
+}
+
+// FP32 far field.  Coordinates stay FP64: the difference x_i - y_j is formed
+// in FP64 and only then rounded to FP32, so adjacent nodes (r ~ 1e-2) in a box
+// of side ~100 keep a relative accuracy of ~1e-7 instead of ~1e-4.  The self
+// pair has r = 0 and (x_i - y_j).q_j = 0; clamping z^2 away from 0 keeps
+// K1(z)/z finite so that pair contributes exactly 0.
+__global__ __launch_bounds__(FAR_BS) void far32_kernel(const double* __restrict__ x,
+                                                       const double* __restrict__ y,
+                                                       const float* __restrict__ wnx,
+                                                       const float* __restrict__ wny,
+                                                       const double* __restrict__ sigma,
+                                                       int64_t N, float kap2, int chunk,
+                                                       float* __restrict__ partial) {
+  __shared__ double2 sxy[FAR_BS];
+  __shared__ float2 sq[FAR_BS];
+  const int64_t i = blockIdx.x * (int64_t)FAR_BS + threadIdx.x;
+  const double xi = i < N ? x[i] : 0.0;
+  const double yi = i < N ? y[i] : 0.0;
+  const int64_t j0 = (int64_t)blockIdx.y * chunk;
+  const int64_t j1 = min(N, j0 + chunk);
+  float acc = 0.0f;
+  for (int64_t jb = j0; jb < j1; jb += FAR_BS) {
+    const int64_t j = jb + threadIdx.x;
+    __syncthreads();
+    if (j < j1) {
+      const float s = (float)sigma[j];
+      sxy[threadIdx.x] = make_double2(x[j], y[j]);
+      sq[threadIdx.x] = make_float2(wnx[j] * s, wny[j] * s);
+    }
+    __syncthreads();
+    const int nb = (int)min((int64_t)FAR_BS, j1 - jb);
+    for (int k = 0; k < nb; ++k) {
+      const double2 p = sxy[k];
+      const float2 q = sq[k];
+      const float dx = (float)(xi - p.x), dy = (float)(yi - p.y);
+      const float z2 = fmaxf(kap2 * fmaf(dx, dx, dy * dy), 1e-30f);
+      acc = fmaf(k1z_32(z2), fmaf(dx, q.x, dy * q.y), acc);
+    }
+  }
+  if (i < N) partial[(int64_t)blockIdx.y * N + i] = acc;
+}
+
+// Gradient far field: grad_x of the double layer,
+// (kappa^2/2pi) [ (K1(z)/z) q - ((x-y).q) (x-y) (K0(z) + 2 K1(z)/z) / r^2 ].
+__global__ __launch_bounds__(FAR_BS) void far_grad64_kernel(GeomView g,
+                                                            const double* __restrict__ sigma,
+                                                            int chunk,
+                                                            double* __restrict__ partial) {
+  __shared__ double2 sxy[FAR_BS];
+  __shared__ double2 sq[FAR_BS];
+  const int64_t N = g.N;
+  const int64_t i = blockIdx.x * (int64_t)FAR_BS + threadIdx.x;
+  const double xi = i < N ? g.x[i] : 0.0;
+  const double yi = i < N ? g.y[i] : 0.0;
+  const double kap2 = g.kappa * g.kappa;
+  const int64_t j0 = (int64_t)blockIdx.y * chunk;
+  const int64_t j1 = min(N, j0 + chunk);
+  double ax = 0.0, ay = 0.0;
+  for (int64_t jb = j0; jb < j1; jb += FAR_BS) {
+    const int64_t j = jb + threadIdx.x;
+    __syncthreads();
+    if (j < j1) {
+      const double s = sigma[j];
+      sxy[threadIdx.x] = make_double2(g.x[j], g.y[j]);
+      sq[threadIdx.x] = make_double2(g.wnx[j] * s, g.wny[j] * s);
+    }
+    __syncthreads();
+    const int nb = (int)min((int64_t)FAR_BS, j1 - jb);
+    for (int k = 0; k < nb; ++k) {
+      const double2 p = sxy[k];
+      const double2 q = sq[k];
+      const double dx = xi - p.x, dy = yi - p.y;
+      const double r2 = fma(dx, dx, dy * dy);
+      if (r2 > 0.0) {
+        double k0, k1z;
+        k0_k1z_64(kap2 * r2, k0, k1z, g.tab);
+        const double dq = fma(dx, q.x, dy * q.y);
+        const double b = dq * (k0 + 2.0 * k1z) * rcp64(r2);
+        ax += k1z * q.x - b * dx;
+        ay += k1z * q.y - b * dy;
+      }
+    }
+  }
+  if (i < N) {
+    partial[((int64_t)blockIdx.y * 2 + 0) * N + i] = ax;
+    partial[((int64_t)blockIdx.y * 2 + 1) * N + i] = ay;
+  }
+}
+
+// out_i = (kappa^2/2pi) sum_chunks partial + sum_window W sigma + sum_extra vals sigma
+__global__ void finish_kernel(GeomView g, int win, int chunks, const double* __restrict__ p64,
+                              const float* __restrict__ p32, const double* __restrict__ W,
+                              const int* __restrict__ xrow, const int* __restrict__ xpan,
+                              const double* __restrict__ xvals, const double* __restrict__ sigma,
+                              double* __restrict__ out) {
+  const int64_t N = g.N;
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  double s = 0.0;
+  if (p64) {
+    for (int c = 0; c < chunks; ++c) s += p64[(int64_t)c * N + i];
+  } else {
+    for (int c = 0; c < chunks; ++c) s += (double)p32[(int64_t)c * N + i];
+  }
+  s *= g.kappa * g.kappa / (2.0 * PI);
+  const int P = g.P;
+  const int64_t pan = i / Q;
+  const int64_t pid = pan / P;
+  const int k = (int)(pan % P);
+  double corr = 0.0;
+  for (int sl = 0; sl <= 2 * win; ++sl) {
+    int kj = (k + sl - win) % P;
+    if (kj < 0) kj += P;
+    const double* sg = sigma + (pid * P + kj) * Q;
+    const double* wr = W + (int64_t)sl * Q * N + i;
+#pragma unroll
+    for (int m = 0; m < Q; ++m) corr = fma(wr[(int64_t)m * N], sg[m], corr);
+  }
+  if (xvals) for (int e = xrow[i]; e < xrow[i + 1]; ++e) {
+    const double* sg = sigma + (int64_t)xpan[e] * Q;
+    const double* vr = xvals + (int64_t)e * Q;
+    for (int m = 0; m < Q; ++m) corr = fma(vr[m], sg[m], corr);
+  }
+  out[i] = s + corr;
+}
+
+__global__ void finish_grad_kernel(GeomView g, int win, int chunks, const double* __restrict__ part,
+                                   const double* __restrict__ WGx, const double* __restrict__ WGy,
+                                   const int* __restrict__ xrow, const int* __restrict__ xpan,
+                                   const double* __restrict__ xg, const double* __restrict__ sigma,
+                                   double* __restrict__ gx, double* __restrict__ gy) {
+  const int64_t N = g.N;
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  double sx = 0.0, sy = 0.0;
+  for (int c = 0; c < chunks; ++c) {
+    sx += part[((int64_t)c * 2 + 0) * N + i];
+    sy += part[((int64_t)c * 2 + 1) * N + i];
+  }
+  const double sc = g.kappa * g.kappa / (2.0 * PI);
+  sx *= sc;
+  sy *= sc;
+  const int P = g.P;
+  const int64_t pan = i / Q;
+  const int64_t pid = pan / P;
+  const int k = (int)(pan % P);
+  for (int sl = 0; sl <= 2 * win; ++sl) {
+    int kj = (k + sl - win) % P;
+    if (kj < 0) kj += P;
+    const double* sg = sigma + (pid * P + kj) * Q;
+    const double* wx = WGx + (int64_t)sl * Q * N + i;
+    const double* wy = WGy + (int64_t)sl * Q * N + i;
+#pragma unroll
+    for (int m = 0; m < Q; ++m) {
+      sx = fma(wx[(int64_t)m * N], sg[m], sx);
+      sy = fma(wy[(int64_t)m * N], sg[m], sy);
+    }
+  }
+  for (int e = xrow[i]; e < xrow[i + 1]; ++e) {
+    const double* sg = sigma + (int64_t)xpan[e] * Q;
+    for (int m = 0; m < Q; ++m) {
+      sx = fma(xg[((int64_t)e * 2 + 0) * Q + m], sg[m], sx);
+      sy = fma(xg[((int64_t)e * 2 + 1) * Q + m], sg[m], sy);
+    }
+  }
+  gx[i] = sx;
+  gy[i] = sy;
+}
+
+void launch_far64(const GeomView& g, const double* sigma, const FarPlan& fp, double* partial,
+                  hipStream_t s) {
+  dim3 grid(fp.tblocks, fp.chunks);
+  far64_kernel<<<grid, FAR_BS, 0, s>>>(g, sigma, fp.chunk, partial);
+  YQ_HIP(hipGetLastError());
+}
+
+void launch_far32(const double* x, const double* y, const float* wnx, const float* wny,
+                  const double* sigma, int64_t N, double kappa, const FarPlan& fp, float* partial,
+                  hipStream_t s) {
+  dim3 grid(fp.tblocks, fp.chunks);
+  far32_kernel<<<grid, FAR_BS, 0, s>>>(x, y, wnx, wny, sigma, N, (float)(kappa * kappa), fp.chunk,
+                                       partial);
+  YQ_HIP(hipGetLastError());
+}
+
+void launch_far_grad64(const GeomView& g, const double* sigma, const FarPlan& fp, double* partial,
+                       hipStream_t s) {
+  dim3 grid(fp.tblocks, fp.chunks);
+  far_grad64_kernel<<<grid, FAR_BS, 0, s>>>(g, sigma, fp.chunk, partial);
+  YQ_HIP(hipGetLastError());
+}
+
+void launch_finish(const GeomView& g, int win, const FarPlan& fp, const double* partial64,
+                   const float* partial32, const double* W, const int* xrow, const int* xpan,
+                   const double* xvals, const double* sigma, double* out, hipStream_t s) {
+  finish_kernel<<<(unsigned)((g.N + 255) / 256), 256, 0, s>>>(g, win, fp.chunks, partial64,
+                                                              partial32, W, xrow, xpan, xvals,
+                                                              sigma, out);
+  YQ_HIP(hipGetLastError());
+}
+
+void launch_finish_grad(const GeomView& g, int win, const FarPlan& fp, const double* partial,
+                        const double* WGx, const double* WGy, const int* xrow, const int* xpan,
+                        const double* xgvals, const double* sigma, double* gx, double* gy,
+                        hipStream_t s) {
+  finish_grad_kernel<<<(unsigned)((g.N + 255) / 256), 256, 0, s>>>(
+      g, win, fp.chunks, partial, WGx, WGy, xrow, xpan, xgvals, sigma, gx, gy);
+  YQ_HIP(hipGetLastError());
+}
+
+}  // namespace yq
