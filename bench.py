@@ -26,11 +26,22 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Algorithmic flops per source-target pair of the far-field kernels (counted
-# from the large-argument branch that almost every pair of this workload takes;
-# an FMA counts 2, every other arithmetic instruction or transcendental 1).
-F_DL32 = 37
-F_DL64 = 81
+# Algorithmic flops per source-target pair of the far-field kernels, counted
+# from the source of the large-argument branch (z >= 2) that almost every pair
+# of this workload takes: an FMA counts 2, every other floating-point
+# arithmetic operation (add, mul, rsq, exp2, rint, ldexp) counts 1.
+#   FP32: 2 FP64 differences, r^2 (3), kappa^2 r^2 (1), rsq (1), z (1), rsq (1),
+#         exp2 argument + exp2 (2), s (1), degree-8 Horner (16), 3 products (3),
+#         (x-y).q (3), accumulate FMA (2)                                    = 36
+#   FP64: differences (2), r^2 (3), kappa^2 r^2 (1), two Newton-refined rsqrt
+#         (2 x 12), z (1), s (1), degree-20 Horner (40), e^-z by Cody-Waite +
+#         degree-13 Taylor (33), 3 products (3), (x-y).q (3), product (1),
+#         accumulate (1)                                                    = 113
+F_DL32 = 36
+F_DL64 = 113
+SRC_FOR_COUNTERS = ["paper_1810_04131_amd/csrc/farfield.hip", "paper_1810_04131_amd/csrc/bessel.h",
+                    "paper_1810_04131_amd/csrc/bessel_tables.h"]
+COUNTERS_FILE = "profiles/far32_kernel_50ellipses_N25600_counters.txt"
 PEAK_FP32 = 157.3e12   # published MI355X FP32 vector peak (needs packed FP32)
 PEAK_FP64 = 78.6e12    # published MI355X FP64 vector peak
 
@@ -44,7 +55,48 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=384)
     ap.add_argument("--fp64-steps", type=int, default=3)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain 256 MiB device-to-device copy (counter calibration)")
     return ap.parse_args()
+
+
+def source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in SRC_FOR_COUNTERS:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_counters(launch_pairs):
+    """HBM bytes per far32 launch from the committed counter summary, or None when
+    the kernel source has changed since the counters were taken."""
+    path = os.path.join(ROOT, COUNTERS_FILE)
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.strip().split("=", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("source_sha256_16") != source_hash():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def copy_probe():
+    import torch
+    n = 64 * 1024 * 1024   # 256 MiB of float32
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": 4 * n, "copy_probe_bytes_written": 4 * n,
+                      "dispatches": 3}))
 
 
 def percentile(xs, q):
@@ -96,6 +148,9 @@ def cpu_baseline(cfg, rows):
 
 def main():
     args = parse()
+    if args.copy_probe:
+        copy_probe()
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}))
@@ -209,7 +264,8 @@ def main():
                       "far64_frac_of_fp64_peak": F_DL64 * pairs / avg64b / PEAK_FP64 if n64b else None},
         "roofline": {"bound": "alu", "kernel": "far32_kernel", "achieved": achieved32 / 1e12,
                      "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s", "frac": achieved32 / PEAK_FP32,
-                     "traffic": None, "flops_per_pair": F_DL32,
+                     "traffic": traffic_from_counters(pairs), "flops_per_pair": F_DL32,
+                     "source_sha256_16": source_hash(),
                      "pairs_per_launch": pairs, "avg_launch_ms": avg32 * 1e3},
     }
     if not args.no_cpu_baseline:
