@@ -171,6 +171,59 @@ int yq_forces(yq_problem* prob, const double* sigma, double gamma, double* force
 int yq_eval_potential(yq_problem* prob, const double* sigma, int64_t M, const double* tx,
                       const double* ty, double* u);
 
+/* ---- Batched solves (step a13) --------------------------------------------------------
+ * A batch holds many independent configurations.  Their nodes are laid out one
+ * after another (configuration c at offset offsets[c] of every batch vector, in
+ * the node order of a single problem) and every GMRES iteration of the whole
+ * batch is one fixed kernel sequence (fused far field over all configurations,
+ * fused correction, batched CGS2 Arnoldi, device-side Givens), captured once as
+ * a hipGraph and replayed.  A configuration's arithmetic depends only on its own
+ * size, so its result is bitwise the same alone (a batch of one) or in a mix.
+ * The batch owns a HIP stream of default priority; every batch call is
+ * synchronous (returns after its work is done) and reads its device inputs when
+ * called, so the caller must have finished writing them. */
+typedef struct yq_batch yq_batch;
+
+int yq_batch_create(const yq_params* params, yq_batch** out);
+void yq_batch_destroy(yq_batch* batch);
+const char* yq_batch_last_error(const yq_batch* batch);
+
+/* nparticles: host [nconf]; center_xy, angle, semi_axes: host, all configurations'
+ * particles concatenated in order (layout as yq_set_particles); kappa: host [nconf].
+ * YQ_EGEOM / YQ_EINVAL name the first failing configuration in the message. */
+int yq_batch_set_configs(yq_batch* batch, int32_t nconf, const int32_t* nparticles,
+                         const double* center_xy, const double* angle, const double* semi_axes,
+                         const double* kappa);
+
+/* total nodes and host offsets [nconf + 1] (may be NULL). */
+int yq_batch_num_nodes(const yq_batch* batch, int64_t* total, int64_t* offsets);
+
+/* As yq_boundary_label / yq_set_boundary_data on every configuration: dev f [total]. */
+int yq_batch_boundary_label(yq_batch* batch, int32_t kind, double param0, double param1,
+                            double* f);
+int yq_batch_set_boundary_data(yq_batch* batch, const double* f);
+
+/* out = (1/2 I + D) sigma for every configuration, one fused launch; dev [total]. */
+int yq_batch_apply_operator(yq_batch* batch, const double* sigma, double* out, int32_t precision);
+
+/* Solves every configuration (FP64, or mixed with FP64 refinement per the
+ * parameters).  dev sigma [total] out; info: host [nconf] (may be NULL).
+ * YQ_ENOCONV if any configuration missed the tolerance. */
+int yq_batch_solve(yq_batch* batch, double* sigma, yq_solve_info* info);
+
+/* Forces and torques of every particle (particles in batch order): dev force
+ * [2 * total particles], dev torque [total particles]; host energy [nconf]. */
+int yq_batch_forces(yq_batch* batch, const double* sigma, double gamma, double* force,
+                    double* torque, double* energy);
+
+/* Autotuner: times the fused FP32 far field for a set of persistent grid sizes
+ * and source-chunk policies on this batch and keeps the fastest (reported in the
+ * two outputs, either may be NULL).  Changes the per-configuration chunking. */
+int yq_batch_autotune(yq_batch* batch, int32_t* persist_blocks, int32_t* far_want);
+
+/* enable != 0: replay the captured iteration graph (default); 0: launch eagerly. */
+int yq_batch_use_graphs(yq_batch* batch, int32_t enable);
+
 /* Per-phase GPU timers: with profiling enabled every launch of a phase is
  * bracketed by hipEvents on the problem's stream.  Phases: 0 FP64 far field,
  * 1 FP32 far field, 2 finish (chunk sum + near correction), 3 gradient far

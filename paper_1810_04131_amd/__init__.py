@@ -14,7 +14,7 @@ from . import _lib
 from ._lib import (YQ_FAR_AUTO, YQ_FAR_DIRECT, YQ_FAR_FMM, YQ_FP64, YQ_LABEL_ARC,  # noqa: F401
                    YQ_LABEL_JANUS, YQ_MIXED, YQError, yq_params, yq_solve_info)
 
-__all__ = ["Problem", "default_params", "bessel", "YQError", "YQ_FP64", "YQ_MIXED"]
+__all__ = ["Problem", "Batch", "default_params", "bessel", "YQError", "YQ_FP64", "YQ_MIXED"]
 
 
 def _torch():
@@ -165,6 +165,124 @@ class Problem:
         self._check(self.lib.yq_eval_potential(self.h, _ptr(sigma), t.shape[0], _ptr(tx), _ptr(ty),
                                                _ptr(u)))
         return u
+
+
+class Batch:
+    """Many independent configurations solved together (a yq_batch handle).
+
+    Batch vectors concatenate the configurations' nodes (offsets[c]..offsets[c+1]).
+    Batch calls are synchronous; the binding synchronises torch's stream first so
+    that inputs written by torch are complete.
+    """
+
+    def __init__(self, params: Optional[yq_params] = None, device: str = "cuda:0", **overrides):
+        torch = _torch()
+        self.torch = torch
+        self.device = torch.device(device)
+        torch.cuda.set_device(self.device)
+        self.lib = _lib.load()
+        self.params = params if params is not None else default_params(**overrides)
+        h = ctypes.c_void_p()
+        _lib.check(self.lib.yq_batch_create(ctypes.byref(self.params), ctypes.byref(h)), None, True)
+        self.h = h
+        self.offsets = None
+        self.total = 0
+        self.nparticles = None
+
+    def _check(self, st):
+        return _lib.check(st, self.h, True)
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            self.lib.yq_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _sync(self):
+        self.torch.cuda.synchronize(self.device)
+
+    def _f64(self, *shape):
+        return self.torch.empty(*shape, dtype=self.torch.float64, device=self.device)
+
+    def _dev(self, t):
+        return self.torch.as_tensor(t, dtype=self.torch.float64, device=self.device).contiguous()
+
+    def set_configs(self, configs):
+        """configs: a list of workloads.Particles-like objects (center, angle, axes, kappa)."""
+        import numpy as np
+        npart = np.ascontiguousarray([c.center.shape[0] for c in configs], dtype=np.int32)
+        cen = np.ascontiguousarray(np.concatenate([np.asarray(c.center, float).reshape(-1) for c in configs]))
+        ang = np.ascontiguousarray(np.concatenate([np.asarray(c.angle, float).reshape(-1) for c in configs]))
+        ax = np.ascontiguousarray(np.concatenate([np.asarray(c.axes, float).reshape(-1) for c in configs]))
+        kap = np.ascontiguousarray([float(c.kappa) for c in configs], dtype=np.float64)
+        vp = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+        self._check(self.lib.yq_batch_set_configs(self.h, len(configs), vp(npart), vp(cen), vp(ang),
+                                                  vp(ax), vp(kap)))
+        tot = ctypes.c_int64()
+        offs = np.zeros(len(configs) + 1, dtype=np.int64)
+        self._check(self.lib.yq_batch_num_nodes(self.h, ctypes.byref(tot), vp(offs)))
+        self.total = int(tot.value)
+        self.offsets = offs
+        self.nparticles = npart
+        return self
+
+    def boundary_label(self, kind=YQ_LABEL_ARC, a=0.7853981633974483, b=0.1):
+        f = self._f64(self.total)
+        self._sync()
+        self._check(self.lib.yq_batch_boundary_label(self.h, kind, float(a), float(b), _ptr(f)))
+        return f
+
+    def set_boundary_data(self, f):
+        f = self._dev(f)
+        self._sync()
+        self._check(self.lib.yq_batch_set_boundary_data(self.h, _ptr(f)))
+        return self
+
+    def apply_operator(self, sigma, precision=YQ_FP64):
+        sigma = self._dev(sigma)
+        out = self._f64(self.total)
+        self._sync()
+        self._check(self.lib.yq_batch_apply_operator(self.h, _ptr(sigma), _ptr(out), precision))
+        return out
+
+    def solve(self, allow_noconv=False):
+        out = self._f64(self.total)
+        n = len(self.offsets) - 1
+        infos = (yq_solve_info * n)()
+        self._sync()
+        st = self.lib.yq_batch_solve(self.h, _ptr(out), infos)
+        if not (allow_noconv and st == _lib.YQ_ENOCONV):
+            self._check(st)
+        return out, [{k: getattr(x, k) for k, _ in x._fields_} for x in infos]
+
+    def forces(self, sigma, gamma=1.0):
+        import numpy as np
+        sigma = self._dev(sigma)
+        npt = int(self.nparticles.sum())
+        F = self._f64(2 * npt)
+        T = self._f64(npt)
+        E = np.zeros(len(self.offsets) - 1)
+        self._sync()
+        self._check(self.lib.yq_batch_forces(self.h, _ptr(sigma), float(gamma), _ptr(F), _ptr(T),
+                                             E.ctypes.data_as(ctypes.c_void_p)))
+        return F.view(npt, 2), T, E
+
+    def autotune(self):
+        pb, fw = ctypes.c_int32(), ctypes.c_int32()
+        self._sync()
+        self._check(self.lib.yq_batch_autotune(self.h, ctypes.byref(pb), ctypes.byref(fw)))
+        return int(pb.value), int(fw.value)
+
+    def use_graphs(self, enable=True):
+        self._check(self.lib.yq_batch_use_graphs(self.h, int(bool(enable))))
+
+    def segment(self, v, c):
+        return v[int(self.offsets[c]):int(self.offsets[c + 1])]
 
 
 def bessel(kind, order, z, precision=YQ_FP64):

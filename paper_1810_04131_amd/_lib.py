@@ -88,6 +88,18 @@ SIGNATURES = {
     "yq_forces": (c_int32, [P, P, c_double, P, P, ctypes.POINTER(c_double)]),
     "yq_eval_potential": (c_int32, [P, P, c_int64, P, P, P]),
     "yq_bessel": (c_int32, [c_int32, c_int32, c_int32, c_int64, P, P]),
+    "yq_batch_create": (c_int32, [ctypes.POINTER(yq_params), ctypes.POINTER(c_void_p)]),
+    "yq_batch_destroy": (None, [P]),
+    "yq_batch_last_error": (c_char_p, [P]),
+    "yq_batch_set_configs": (c_int32, [P, c_int32, P, P, P, P, P]),
+    "yq_batch_num_nodes": (c_int32, [P, ctypes.POINTER(c_int64), P]),
+    "yq_batch_boundary_label": (c_int32, [P, c_int32, c_double, c_double, P]),
+    "yq_batch_set_boundary_data": (c_int32, [P, P]),
+    "yq_batch_apply_operator": (c_int32, [P, P, P, c_int32]),
+    "yq_batch_solve": (c_int32, [P, P, P]),
+    "yq_batch_forces": (c_int32, [P, P, c_double, P, P, P]),
+    "yq_batch_autotune": (c_int32, [P, ctypes.POINTER(c_int32), ctypes.POINTER(c_int32)]),
+    "yq_batch_use_graphs": (c_int32, [P, c_int32]),
     "yq_profile_enable": (c_int32, [P, c_int32]),
     "yq_profile_read": (c_int32, [P, c_int32, ctypes.POINTER(c_int64), ctypes.POINTER(c_double),
                                   c_int32]),
@@ -118,11 +130,11 @@ def load():
     return lib
 
 
-def check(status, handle=None):
+def check(status, handle=None, batch=False):
     if status == YQ_OK:
         return status
     lib = load()
-    detail = lib.yq_last_error(handle)
+    detail = lib.yq_batch_last_error(handle) if batch else lib.yq_last_error(handle)
     detail = detail.decode() if detail else ""
     base = lib.yq_error_string(status).decode()
     raise YQError(status, f"{base}: {detail}")

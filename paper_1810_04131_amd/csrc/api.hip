@@ -8,83 +8,9 @@
 #include <numeric>
 
 #include "common.h"
+#include "problem.h"
 
 using namespace yq;
-
-struct yq_problem {
-  yq_params prm{};
-  hipStream_t stream = nullptr;
-  std::string err;
-
-  int n = 0;
-  int64_t N = 0;
-  double kappa = 0.0;
-  bool ready = false;
-  bool have_f = false;
-
-  std::vector<double> h_pc;  // [n*5]
-  DevBuf<double> pc, x, y, nx, ny, w, wnx, wny, panel_h, pcx, pcy, pr;
-  DevBuf<float> wnx32, wny32;
-  DevBuf<double> pot_partial;
-  DevBuf<int> nb_ptr, nb_idx, bad;
-  DevBuf<int> xrow, xpan;
-  int64_t x_total = 0;
-  DevBuf<double> xvals, xgvals;
-  DevBuf<double> W, WGx, WGy;
-  DevBuf<double> Lqbx, Lnear, Lpot, tab;
-  Consts consts{};
-  FarPlan fp{};
-  DevBuf<double> partial, gpartial;
-  DevBuf<float> partial32;
-  DevBuf<double> f;
-  // Krylov workspace
-  DevBuf<double> V, kw, kr, kd, kpart, kred;
-  DevBuf<double> gx, gy, en;
-
-  // per-phase timers
-  static constexpr int NPHASE = 6;
-  bool prof = false;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[NPHASE];
-  std::vector<hipEvent_t> pool;
-
-  hipEvent_t event() {
-    if (!pool.empty()) {
-      hipEvent_t e = pool.back();
-      pool.pop_back();
-      return e;
-    }
-    hipEvent_t e;
-    YQ_HIP(hipEventCreate(&e));
-    return e;
-  }
-  ~yq_problem() {
-    for (auto& v : ev)
-      for (auto& p : v) {
-        (void)hipEventDestroy(p.first);
-        (void)hipEventDestroy(p.second);
-      }
-    for (auto e : pool) (void)hipEventDestroy(e);
-  }
-
-  GeomView view() const {
-    GeomView g;
-    g.n = n;
-    g.P = prm.panels_per_particle;
-    g.N = N;
-    g.kappa = kappa;
-    g.pc = pc.p;
-    g.x = x.p;
-    g.y = y.p;
-    g.nx = nx.p;
-    g.ny = ny.p;
-    g.w = w.p;
-    g.wnx = wnx.p;
-    g.wny = wny.p;
-    g.panel_h = panel_h.p;
-    g.tab = tab.p;
-    return g;
-  }
-};
 
 namespace {
 
@@ -533,15 +459,17 @@ int yq_set_particles(yq_problem* pb, int32_t n, const double* center_xy, const d
     launch_to_f32(pb->wnx.p, pb->wnx32.p, N, s);
     launch_to_f32(pb->wny.p, pb->wny32.p, N, s);
 
-    pb->fp = far_plan(N, N, 256);
+    pb->fp = far_plan(N, N, 256, pb->far_want);
     pb->partial.alloc((size_t)pb->fp.chunks * N);
     pb->partial32.alloc((size_t)pb->fp.chunks * N);
-    pb->gpartial.alloc((size_t)pb->fp.chunks * 2 * N);
     pb->f.alloc(N);
-    pb->gx.alloc(N);
-    pb->gy.alloc(N);
     pb->en.alloc(n);
-    ensure_krylov(pb);
+    if (!pb->batch_member) {
+      pb->gpartial.alloc((size_t)pb->fp.chunks * 2 * N);
+      pb->gx.alloc(N);
+      pb->gy.alloc(N);
+      ensure_krylov(pb);
+    }
     YQ_HIP(hipStreamSynchronize(s));
     pb->ready = true;
   });
@@ -716,6 +644,7 @@ int yq_surface_gradient(yq_problem* pb, const double* sigma, double* gx, double*
   return guarded(pb, [&] {
     require_ready(pb);
     YQ_REQUIRE(sigma && gx && gy, YQ_EINVAL, "null argument");
+    pb->gpartial.reserve((size_t)pb->fp.chunks * 2 * pb->N);
     GeomView g = pb->view();
     {
       Timed t(pb, 3);
@@ -732,6 +661,9 @@ int yq_forces(yq_problem* pb, const double* sigma, double gamma, double* force, 
     require_ready(pb);
     YQ_REQUIRE(sigma && force && torque, YQ_EINVAL, "null argument");
     YQ_REQUIRE(pb->have_f, YQ_ESTATE, "boundary data not set");
+    pb->gpartial.reserve((size_t)pb->fp.chunks * 2 * pb->N);
+    pb->gx.reserve(pb->N);
+    pb->gy.reserve(pb->N);
     GeomView g = pb->view();
     {
       Timed t(pb, 3);

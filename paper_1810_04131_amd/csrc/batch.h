@@ -1,0 +1,80 @@
+// Internal batch engine (batch.hip): fused kernels over many configurations.
+#pragma once
+
+#include <vector>
+
+#include "common.h"
+#include "problem.h"
+
+namespace yq {
+
+// What the fused kernels need of one configuration (device copy, one per config).
+struct ConfDev {
+  const double* x;
+  const double* y;
+  const double* wnx;
+  const double* wny;
+  const float* wnx32;
+  const float* wny32;
+  const double* W;
+  const int* xrow;
+  const int* xpan;
+  const double* xvals;
+  const double* tab;
+  double* part64;
+  float* part32;
+  int64_t N;      // nodes
+  int64_t off;    // offset of its nodes in the arena vectors
+  double kappa;
+  double kap2;
+  int P, win;
+  int tblocks, chunks, chunk;
+  int kb;         // Krylov reduction blocks
+  int64_t kpoff;  // offset of its multi-dot partials
+};
+
+struct Member {
+  yq_problem* pb = nullptr;  // not owned
+  int64_t off = 0;
+};
+
+struct Engine {
+  yq_params prm{};
+  int m = 100;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  bool use_graphs = true;
+  int persist_blocks = 0;   // 0: default (2048)
+  int64_t T = 0;            // arena capacity (nodes)
+  std::vector<Member> members;
+
+  DevBuf<ConfDev> conf;
+  DevBuf<int4> items;
+  DevBuf<int2> kblk;
+  DevBuf<int> node_conf;
+  int nitems = 0, nkblk = 0;
+  DevBuf<double> kpart;
+  DevBuf<int> active, inc, jc, kc, conv;
+  DevBuf<double> hb, H, cs, sn, gv, yv, scale, bnorm, rtol, res, nrm;
+  DevBuf<double> V, w, r, tmp, delta, f;
+  hipGraphExec_t graph_exec[2] = {nullptr, nullptr};
+
+  ~Engine();
+  void init(const yq_params& p);
+  void rebuild();
+  int grid_blocks() const;
+  void matvec(int prec, const int* mask, const double* Vin, const int* col, double* out);
+  void dots(const int* mask, const double* x, const double* y);
+  void axpby(const int* mask, double a, const double* x, double b, const double* y, double* out);
+  void iteration(int prec);
+  void run_iteration(int prec);
+  int count_active(std::vector<int>& h);
+  std::vector<double> read_nrm();
+  void upload_mask(DevBuf<int>& d, const std::vector<int>& h);
+  void gmres(int prec, const double* b, double* x, const std::vector<int>& incl,
+             const std::vector<double>& tolv, std::vector<int>& iters, std::vector<int>& budget,
+             std::vector<int>& converged, int& matvecs);
+  void solve(std::vector<yq_solve_info>& info, double* x_out);
+};
+
+}  // namespace yq

@@ -1,0 +1,676 @@
+// Step a13: many independent configurations solved together.
+//
+// Each configuration is an ordinary problem (geometry, near lists and QBX
+// correction built by yq_set_particles).  Its node range lives at a fixed
+// offset of an arena of capacity T nodes; the Krylov basis and all batch
+// vectors are arena-sized and column-major (V[k * T + g]).
+//
+// Per GMRES iteration the whole batch runs as one fixed kernel sequence:
+//   fused far field   persistent blocks over a static work list of
+//                     (configuration, target tile, source chunk) items,
+//   fused finish      chunk reduction + QBX window correction for every node,
+//   CGS2 Arnoldi      per-configuration multi-dots (fixed row blocks), reduce,
+//                     update, twice, then the norm,
+//   Givens            one thread per configuration (device-side Hessenberg,
+//                     rotations, residual estimate, convergence mask),
+//   scale             the next basis vector.
+// Every kernel reads the per-configuration column index and active mask from
+// device memory, so the sequence is captured once as a hipGraph and replayed
+// for every iteration; converged configurations drop out through the mask.
+// A configuration's far-field plan and reduction blocks depend only on its own
+// size, so its arithmetic -- and result -- is the same alone or in any mix.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <numeric>
+
+#include "bessel.h"
+#include "common.h"
+#include "farfield_core.h"
+#include "problem.h"
+#include "batch.h"
+
+namespace yq {
+
+constexpr int BB = 256;    // far-field block
+constexpr int KR = 4096;   // rows per Krylov reduction block
+constexpr int KB2 = 256;   // Krylov block size
+
+// ---- fused far field ----------------------------------------------------------------------
+
+__global__ __launch_bounds__(BB) void bfar64_kernel(const ConfDev* __restrict__ cf,
+                                                    const int4* __restrict__ items, int nitems,
+                                                    const int* __restrict__ mask,
+                                                    const double* __restrict__ V,
+                                                    const int* __restrict__ col, int64_t T) {
+  __shared__ double2 sxy[BB];
+  __shared__ double2 sq[BB];
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const int4 w = items[it];
+    const int c = w.x;
+    if (!mask[c]) continue;
+    const ConfDev& cd = cf[c];
+    const int64_t N = cd.N;
+    const double* sg = V + (col ? (int64_t)col[c] * T : 0) + cd.off;
+    const int64_t i = (int64_t)w.y * BB + threadIdx.x;
+    const double xi = i < N ? cd.x[i] : 0.0;
+    const double yi = i < N ? cd.y[i] : 0.0;
+    const int64_t j0 = (int64_t)w.z * cd.chunk;
+    const int64_t j1 = min(N, j0 + cd.chunk);
+    double acc = 0.0;
+    for (int64_t jb = j0; jb < j1; jb += BB) {
+      const int64_t j = jb + threadIdx.x;
+      __syncthreads();
+      if (j < j1) {
+        const double s = sg[j];
+        sxy[threadIdx.x] = make_double2(cd.x[j], cd.y[j]);
+        sq[threadIdx.x] = make_double2(cd.wnx[j] * s, cd.wny[j] * s);
+      }
+      __syncthreads();
+      const int nb = (int)min((int64_t)BB, j1 - jb);
+      acc = far64_tile(xi, yi, sxy, sq, nb, cd.kap2, cd.tab, acc);
+    }
+    if (i < N) cd.part64[(int64_t)w.z * N + i] = acc;
+  }
+}
+
+__global__ __launch_bounds__(BB) void bfar32_kernel(const ConfDev* __restrict__ cf,
+                                                    const int4* __restrict__ items, int nitems,
+                                                    const int* __restrict__ mask,
+                                                    const double* __restrict__ V,
+                                                    const int* __restrict__ col, int64_t T) {
+  __shared__ double2 sxy[BB];
+  __shared__ float2 sq[BB];
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const int4 w = items[it];
+    const int c = w.x;
+    if (!mask[c]) continue;
+    const ConfDev& cd = cf[c];
+    const int64_t N = cd.N;
+    const double* sg = V + (col ? (int64_t)col[c] * T : 0) + cd.off;
+    const int64_t i = (int64_t)w.y * BB + threadIdx.x;
+    const double xi = i < N ? cd.x[i] : 0.0;
+    const double yi = i < N ? cd.y[i] : 0.0;
+    const int64_t j0 = (int64_t)w.z * cd.chunk;
+    const int64_t j1 = min(N, j0 + cd.chunk);
+    float acc = 0.0f;
+    const float kap2 = (float)cd.kap2;
+    for (int64_t jb = j0; jb < j1; jb += BB) {
+      const int64_t j = jb + threadIdx.x;
+      __syncthreads();
+      if (j < j1) {
+        const float s = (float)sg[j];
+        sxy[threadIdx.x] = make_double2(cd.x[j], cd.y[j]);
+        sq[threadIdx.x] = make_float2(cd.wnx32[j] * s, cd.wny32[j] * s);
+      }
+      __syncthreads();
+      const int nb = (int)min((int64_t)BB, j1 - jb);
+      acc = far32_tile(xi, yi, sxy, sq, nb, kap2, acc);
+    }
+    if (i < N) cd.part32[(int64_t)w.z * N + i] = acc;
+  }
+}
+
+// out[g] = (kappa^2/2pi) sum_chunks partial + correction, for every node of an active config.
+__global__ void bfinish_kernel(const ConfDev* __restrict__ cf, const int* __restrict__ node_conf,
+                               int64_t T, const int* __restrict__ mask, int f32,
+                               const double* __restrict__ V, const int* __restrict__ col,
+                               double* __restrict__ out) {
+  const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (g >= T) return;
+  const int c = node_conf[g];
+  if (c < 0 || !mask[c]) return;
+  const ConfDev& cd = cf[c];
+  const int64_t N = cd.N;
+  const int64_t i = g - cd.off;
+  const double* sg = V + (col ? (int64_t)col[c] * T : 0) + cd.off;
+  double s = 0.0;
+  if (!f32) {
+    for (int k = 0; k < cd.chunks; ++k) s += cd.part64[(int64_t)k * N + i];
+  } else {
+    for (int k = 0; k < cd.chunks; ++k) s += (double)cd.part32[(int64_t)k * N + i];
+  }
+  s *= cd.kappa * cd.kappa / (2.0 * PI);
+  const double corr = correction_row(i, N, cd.P, cd.win, cd.W, cd.xrow, cd.xpan, cd.xvals, sg);
+  out[g] = s + corr;
+}
+
+// ---- batched Krylov kernels -------------------------------------------------------------------
+
+__device__ __forceinline__ double bsum(double v, double* sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int o = KB2 / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+// partial[kpoff + k*kb + lb] = sum_{rows of block lb} A[k*lda + off + i] * w[off + i],
+// k < (jc ? jc[c] + 1 : 1).
+__global__ __launch_bounds__(KB2) void bmultidot_kernel(const ConfDev* __restrict__ cf,
+                                                        const int2* __restrict__ blk,
+                                                        const double* __restrict__ A, int64_t lda,
+                                                        const int* __restrict__ jc,
+                                                        const double* __restrict__ w,
+                                                        const int* __restrict__ mask,
+                                                        double* __restrict__ partial) {
+  __shared__ double sh[KB2];
+  const int2 b = blk[blockIdx.x];
+  const int c = b.x;
+  if (!mask[c]) return;
+  const ConfDev& cd = cf[c];
+  const int kc = jc ? jc[c] + 1 : 1;
+  const int64_t r0 = (int64_t)b.y * KR;
+  const int64_t r1 = min(cd.N, r0 + KR);
+  const double* wv = w + cd.off;
+  for (int k = 0; k < kc; ++k) {
+    const double* a = A + (int64_t)k * lda + cd.off;
+    double acc = 0.0;
+    for (int64_t i = r0 + threadIdx.x; i < r1; i += KB2) acc = fma(a[i], wv[i], acc);
+    const double s = bsum(acc, sh);
+    if (threadIdx.x == 0) partial[cd.kpoff + (int64_t)k * cd.kb + b.y] = s;
+  }
+}
+
+// out[c*stride + off + k] = sum_lb partial[kpoff + k*kb + lb]
+__global__ void breduce_kernel(const ConfDev* __restrict__ cf, int nconf, int kmax,
+                               const int* __restrict__ jc, const int* __restrict__ mask,
+                               const double* __restrict__ partial, double* __restrict__ out,
+                               int stride, int off) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = t / kmax, k = t % kmax;
+  if (c >= nconf || !mask[c]) return;
+  const int kc = jc ? jc[c] + 1 : 1;
+  if (k >= kc) return;
+  const ConfDev& cd = cf[c];
+  double s = 0.0;
+  for (int lb = 0; lb < cd.kb; ++lb) s += partial[cd.kpoff + (int64_t)k * cd.kb + lb];
+  out[(int64_t)c * stride + off + k] = s;
+}
+
+// w[g] += alpha * sum_{k < ncols(c)} V[k*T + g] * h[c*stride + off + k];
+// ncols = jc[c] + 1 (Arnoldi) or kc[c] (solution update).
+__global__ void bupdate_kernel(const int* __restrict__ node_conf, int64_t T,
+                               const int* __restrict__ mask, const int* __restrict__ jc,
+                               const int* __restrict__ kc, const double* __restrict__ V,
+                               const double* __restrict__ h, int stride, int off, double alpha,
+                               double* __restrict__ w) {
+  const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (g >= T) return;
+  const int c = node_conf[g];
+  if (c < 0 || !mask[c]) return;
+  const int n = jc ? jc[c] + 1 : kc[c];
+  const double* hc = h + (int64_t)c * stride + off;
+  double s = 0.0;
+  for (int k = 0; k < n; ++k) s = fma(V[(int64_t)k * T + g], hc[k], s);
+  w[g] = fma(alpha, s, w[g]);
+}
+
+// Device-side Arnoldi bookkeeping, one thread per configuration.
+__global__ void bgivens_kernel(int nconf, int m, int* __restrict__ active, int* __restrict__ jc,
+                               int* __restrict__ kc, const double* __restrict__ hb, int hstride,
+                               double* __restrict__ H, double* __restrict__ cs,
+                               double* __restrict__ sn, double* __restrict__ gv,
+                               double* __restrict__ scale, const double* __restrict__ bnorm,
+                               const double* __restrict__ rtol, double* __restrict__ res,
+                               int* __restrict__ conv) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nconf || !active[c]) return;
+  const int j = jc[c];
+  const double* h = hb + (int64_t)c * hstride;
+  double* Hc = H + (int64_t)c * (m + 1) * m;
+  double* col = Hc + (int64_t)j * (m + 1);
+  double* csc = cs + (int64_t)c * m;
+  double* snc = sn + (int64_t)c * m;
+  double* g = gv + (int64_t)c * (m + 1);
+  for (int i = 0; i <= j; ++i) col[i] = h[i] + h[m + 1 + i];
+  const double hn = sqrt(fmax(h[2 * (m + 1)], 0.0));
+  col[j + 1] = hn;
+  for (int i = 0; i < j; ++i) {
+    const double t = csc[i] * col[i] + snc[i] * col[i + 1];
+    col[i + 1] = -snc[i] * col[i] + csc[i] * col[i + 1];
+    col[i] = t;
+  }
+  const double den = hypot(col[j], col[j + 1]);
+  csc[j] = den > 0.0 ? col[j] / den : 1.0;
+  snc[j] = den > 0.0 ? col[j + 1] / den : 0.0;
+  col[j] = den;
+  col[j + 1] = 0.0;
+  g[j + 1] = -snc[j] * g[j];
+  g[j] = csc[j] * g[j];
+  const double r = fabs(g[j + 1]) / bnorm[c];
+  res[c] = r;
+  jc[c] = j + 1;
+  kc[c] = j + 1;
+  scale[c] = hn > 0.0 ? 1.0 / hn : 0.0;
+  if (r <= rtol[c] || hn == 0.0 || j + 1 >= m) {
+    active[c] = 0;
+    conv[c] = r <= rtol[c] ? 1 : 0;
+  }
+}
+
+// V[jc[c]*T + g] = w[g] * scale[c] for active configurations.
+__global__ void bscale_kernel(const int* __restrict__ node_conf, int64_t T,
+                              const int* __restrict__ mask, const int* __restrict__ jc,
+                              const double* __restrict__ scale, const double* __restrict__ w,
+                              double* __restrict__ V) {
+  const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (g >= T) return;
+  const int c = node_conf[g];
+  if (c < 0 || !mask[c]) return;
+  V[(int64_t)jc[c] * T + g] = w[g] * scale[c];
+}
+
+// y = H^-1 g for the kc[c] columns of the finished cycle.
+__global__ void bsolve_kernel(int nconf, int m, const int* __restrict__ mask,
+                              const int* __restrict__ kc, const double* __restrict__ H,
+                              const double* __restrict__ gv, double* __restrict__ y) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nconf || !mask[c]) return;
+  const int k = kc[c];
+  const double* Hc = H + (int64_t)c * (m + 1) * m;
+  const double* g = gv + (int64_t)c * (m + 1);
+  double* yc = y + (int64_t)c * m;
+  for (int i = k - 1; i >= 0; --i) {
+    double t = g[i];
+    for (int q = i + 1; q < k; ++q) t -= Hc[(int64_t)q * (m + 1) + i] * yc[q];
+    yc[i] = t / Hc[(int64_t)i * (m + 1) + i];
+  }
+}
+
+// out = a*x + b*y on the nodes of masked configurations (y may be null).
+__global__ void baxpby_kernel(const int* __restrict__ node_conf, int64_t T,
+                              const int* __restrict__ mask, double a, const double* __restrict__ x,
+                              double b, const double* __restrict__ y, double* __restrict__ out) {
+  const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (g >= T) return;
+  const int c = node_conf[g];
+  if (c < 0 || !mask[c]) return;
+  out[g] = a * x[g] + (y ? b * y[g] : 0.0);
+}
+
+static inline unsigned nb256(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+// ---- host engine -----------------------------------------------------------------------------
+
+Engine::~Engine() {
+  for (auto& g : graph_exec)
+    if (g) (void)hipGraphExecDestroy(g);
+  if (own_stream && stream) (void)hipStreamDestroy(stream);
+}
+
+void Engine::init(const yq_params& p) {
+  prm = p;
+  m = p.restart;
+  if (!stream) {
+    YQ_HIP(hipStreamCreate(&stream));  // default priority
+    own_stream = true;
+  }
+}
+
+// Rebuilds the descriptors, work lists and per-configuration reduction blocks.
+void Engine::rebuild() {
+  const int nc = (int)members.size();
+  std::vector<ConfDev> h(nc);
+  std::vector<int4> it;
+  std::vector<int2> kb;
+  std::vector<int> nconf_of((size_t)T, -1);
+  int64_t kpoff = 0;
+  for (int c = 0; c < nc; ++c) {
+    Member& mb = members[c];
+    yq_problem* pb = mb.pb;
+    ConfDev& d = h[c];
+    std::memset(&d, 0, sizeof(d));
+    if (pb) {
+      d.x = pb->x.p;
+      d.y = pb->y.p;
+      d.wnx = pb->wnx.p;
+      d.wny = pb->wny.p;
+      d.wnx32 = pb->wnx32.p;
+      d.wny32 = pb->wny32.p;
+      d.W = pb->W.p;
+      d.xrow = pb->xrow.p;
+      d.xpan = pb->xpan.p;
+      d.xvals = pb->x_total > 0 ? pb->xvals.p : nullptr;
+      d.tab = pb->tab.p;
+      d.part64 = pb->partial.p;
+      d.part32 = pb->partial32.p;
+      d.N = pb->N;
+      d.off = mb.off;
+      d.kappa = pb->kappa;
+      d.kap2 = pb->kappa * pb->kappa;
+      d.P = pb->prm.panels_per_particle;
+      d.win = pb->prm.qbx_window;
+      d.tblocks = pb->fp.tblocks;
+      d.chunks = pb->fp.chunks;
+      d.chunk = pb->fp.chunk;
+      d.kb = (int)((pb->N + KR - 1) / KR);
+      d.kpoff = kpoff;
+      kpoff += (int64_t)(m + 1) * d.kb;
+      for (int t = 0; t < d.tblocks; ++t)
+        for (int s = 0; s < d.chunks; ++s) it.push_back(make_int4(c, t, s, 0));
+      for (int b = 0; b < d.kb; ++b) kb.push_back(make_int2(c, b));
+      for (int64_t i = 0; i < d.N; ++i) nconf_of[mb.off + i] = c;
+    }
+  }
+  nitems = (int)it.size();
+  nkblk = (int)kb.size();
+  conf.alloc(std::max(nc, 1));
+  items.alloc(std::max(nitems, 1));
+  kblk.alloc(std::max(nkblk, 1));
+  node_conf.alloc(std::max<int64_t>(T, 1));
+  kpart.alloc(std::max<int64_t>(kpoff, 1));
+  if (nc) YQ_HIP(hipMemcpyAsync(conf.p, h.data(), nc * sizeof(ConfDev), hipMemcpyHostToDevice, stream));
+  if (nitems) YQ_HIP(hipMemcpyAsync(items.p, it.data(), nitems * sizeof(int4), hipMemcpyHostToDevice, stream));
+  if (nkblk) YQ_HIP(hipMemcpyAsync(kblk.p, kb.data(), nkblk * sizeof(int2), hipMemcpyHostToDevice, stream));
+  if (T) YQ_HIP(hipMemcpyAsync(node_conf.p, nconf_of.data(), T * sizeof(int), hipMemcpyHostToDevice, stream));
+  // per-configuration state
+  const int hs = 2 * (m + 1) + 2;
+  active.alloc(std::max(nc, 1));
+  inc.alloc(std::max(nc, 1));
+  jc.alloc(std::max(nc, 1));
+  kc.alloc(std::max(nc, 1));
+  conv.alloc(std::max(nc, 1));
+  hb.alloc((size_t)std::max(nc, 1) * hs);
+  H.alloc((size_t)std::max(nc, 1) * (m + 1) * m);
+  cs.alloc((size_t)std::max(nc, 1) * m);
+  sn.alloc((size_t)std::max(nc, 1) * m);
+  gv.alloc((size_t)std::max(nc, 1) * (m + 1));
+  yv.alloc((size_t)std::max(nc, 1) * m);
+  scale.alloc(std::max(nc, 1));
+  bnorm.alloc(std::max(nc, 1));
+  rtol.alloc(std::max(nc, 1));
+  res.alloc(std::max(nc, 1));
+  nrm.alloc(std::max(nc, 1));
+  V.reserve((size_t)(m + 1) * std::max<int64_t>(T, 1));
+  w.reserve(std::max<int64_t>(T, 1));
+  r.reserve(std::max<int64_t>(T, 1));
+  tmp.reserve(std::max<int64_t>(T, 1));
+  delta.reserve(std::max<int64_t>(T, 1));
+  f.reserve(std::max<int64_t>(T, 1));
+  for (auto& g : graph_exec)
+    if (g) {
+      (void)hipGraphExecDestroy(g);
+      g = nullptr;
+    }
+  YQ_HIP(hipStreamSynchronize(stream));
+}
+
+int Engine::grid_blocks() const {
+  const int want = persist_blocks > 0 ? persist_blocks : 2048;
+  return std::max(1, std::min(nitems, want));
+}
+
+// out = A sigma (precision prec) for configurations in mask; input column from V/col.
+void Engine::matvec(int prec, const int* mask, const double* Vin, const int* col, double* out) {
+  if (nitems == 0) return;
+  if (prec == YQ_MIXED)
+    bfar32_kernel<<<grid_blocks(), BB, 0, stream>>>(conf.p, items.p, nitems, mask, Vin, col, T);
+  else
+    bfar64_kernel<<<grid_blocks(), BB, 0, stream>>>(conf.p, items.p, nitems, mask, Vin, col, T);
+  YQ_HIP(hipGetLastError());
+  bfinish_kernel<<<nb256(T), 256, 0, stream>>>(conf.p, node_conf.p, T, mask, prec == YQ_MIXED, Vin,
+                                               col, out);
+  YQ_HIP(hipGetLastError());
+}
+
+// nrm[c] = x_c . y_c for masked configurations (device)
+void Engine::dots(const int* mask, const double* x, const double* y) {
+  const int nc = (int)members.size();
+  if (nkblk == 0) return;
+  bmultidot_kernel<<<nkblk, KB2, 0, stream>>>(conf.p, kblk.p, x, 0, nullptr, y, mask, kpart.p);
+  YQ_HIP(hipGetLastError());
+  breduce_kernel<<<nb256(nc), 256, 0, stream>>>(conf.p, nc, 1, nullptr, mask, kpart.p, nrm.p, 1, 0);
+  YQ_HIP(hipGetLastError());
+}
+
+void Engine::axpby(const int* mask, double a, const double* x, double b, const double* y,
+                   double* out) {
+  baxpby_kernel<<<nb256(T), 256, 0, stream>>>(node_conf.p, T, mask, a, x, b, y, out);
+  YQ_HIP(hipGetLastError());
+}
+
+// One Arnoldi step for every active configuration (the captured sequence).
+void Engine::iteration(int prec) {
+  const int nc = (int)members.size();
+  const int hs = 2 * (m + 1) + 2;
+  matvec(prec, active.p, V.p, jc.p, w.p);
+  for (int pass = 0; pass < 2; ++pass) {
+    bmultidot_kernel<<<nkblk, KB2, 0, stream>>>(conf.p, kblk.p, V.p, T, jc.p, w.p, active.p,
+                                                kpart.p);
+    breduce_kernel<<<nb256((int64_t)nc * (m + 1)), 256, 0, stream>>>(
+        conf.p, nc, m + 1, jc.p, active.p, kpart.p, hb.p, hs, pass * (m + 1));
+    bupdate_kernel<<<nb256(T), 256, 0, stream>>>(node_conf.p, T, active.p, jc.p, nullptr, V.p,
+                                                 hb.p, hs, pass * (m + 1), -1.0, w.p);
+  }
+  bmultidot_kernel<<<nkblk, KB2, 0, stream>>>(conf.p, kblk.p, w.p, 0, nullptr, w.p, active.p,
+                                              kpart.p);
+  breduce_kernel<<<nb256(nc), 256, 0, stream>>>(conf.p, nc, 1, nullptr, active.p, kpart.p, hb.p, hs,
+                                                2 * (m + 1));
+  bgivens_kernel<<<nb256(nc), 256, 0, stream>>>(nc, m, active.p, jc.p, kc.p, hb.p, hs, H.p, cs.p,
+                                                sn.p, gv.p, scale.p, bnorm.p, rtol.p, res.p,
+                                                conv.p);
+  bscale_kernel<<<nb256(T), 256, 0, stream>>>(node_conf.p, T, active.p, jc.p, scale.p, w.p, V.p);
+  YQ_HIP(hipGetLastError());
+}
+
+void Engine::run_iteration(int prec) {
+  const int gi = prec == YQ_MIXED ? 1 : 0;
+  if (!use_graphs) {
+    iteration(prec);
+    return;
+  }
+  if (!graph_exec[gi]) {
+    hipGraph_t graph;
+    YQ_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+    iteration(prec);
+    YQ_HIP(hipStreamEndCapture(stream, &graph));
+    YQ_HIP(hipGraphInstantiate(&graph_exec[gi], graph, nullptr, nullptr, 0));
+    YQ_HIP(hipGraphDestroy(graph));
+  }
+  YQ_HIP(hipGraphLaunch(graph_exec[gi], stream));
+}
+
+int Engine::count_active(std::vector<int>& h) {
+  const int nc = (int)members.size();
+  h.resize(nc);
+  YQ_HIP(hipMemcpyAsync(h.data(), active.p, nc * sizeof(int), hipMemcpyDeviceToHost, stream));
+  YQ_HIP(hipStreamSynchronize(stream));
+  int n = 0;
+  for (int v : h) n += v;
+  return n;
+}
+
+std::vector<double> Engine::read_nrm() {
+  const int nc = (int)members.size();
+  std::vector<double> h(nc);
+  YQ_HIP(hipMemcpyAsync(h.data(), nrm.p, nc * sizeof(double), hipMemcpyDeviceToHost, stream));
+  YQ_HIP(hipStreamSynchronize(stream));
+  return h;
+}
+
+void Engine::upload_mask(DevBuf<int>& d, const std::vector<int>& h) {
+  YQ_HIP(hipMemcpyAsync(d.p, h.data(), h.size() * sizeof(int), hipMemcpyHostToDevice, stream));
+}
+
+// Batched restarted GMRES: solve A x_c = b_c (x zero on entry) for configurations in incl.
+// Per configuration: relative tolerance tolv[c], iteration budget budget[c] (updated).
+void Engine::gmres(int prec, const double* b, double* x, const std::vector<int>& incl,
+                   const std::vector<double>& tolv, std::vector<int>& iters,
+                   std::vector<int>& budget, std::vector<int>& converged, int& matvecs) {
+  const int nc = (int)members.size();
+  std::vector<int> part(incl);
+  converged.assign(nc, 0);
+  upload_mask(inc, part);
+  axpby(inc.p, 0.0, b, 0.0, nullptr, x);
+  axpby(inc.p, 1.0, b, 0.0, nullptr, r.p);
+  dots(inc.p, b, b);
+  std::vector<double> bn = read_nrm();
+  for (double& v : bn) v = std::sqrt(std::max(v, 0.0));
+  std::vector<int> hact;
+  bool first = true;
+  while (true) {
+    if (!first) {
+      // r = b - A x for configurations still running
+      upload_mask(inc, part);
+      matvec(prec, inc.p, x, nullptr, tmp.p);
+      ++matvecs;
+      axpby(inc.p, 1.0, b, -1.0, tmp.p, r.p);
+    }
+    first = false;
+    dots(inc.p, r.p, r.p);
+    std::vector<double> beta = read_nrm();
+    std::vector<int> act(nc, 0);
+    std::vector<double> sc(nc, 0.0), g0((size_t)nc * (m + 1), 0.0), bnv(nc, 1.0), rt(nc, 0.0);
+    int nact = 0;
+    for (int c = 0; c < nc; ++c) {
+      if (!part[c]) continue;
+      const double bt = std::sqrt(std::max(beta[c], 0.0));
+      if (bn[c] == 0.0 || bt / bn[c] <= tolv[c]) {
+        converged[c] = 1;
+        part[c] = 0;
+        continue;
+      }
+      if (budget[c] <= 0) {
+        part[c] = 0;
+        continue;
+      }
+      act[c] = 1;
+      ++nact;
+      sc[c] = 1.0 / bt;
+      g0[(size_t)c * (m + 1)] = bt;
+      bnv[c] = bn[c];
+      rt[c] = tolv[c];
+    }
+    if (nact == 0) break;
+    std::vector<int> zeros(nc, 0);
+    upload_mask(active, act);
+    upload_mask(jc, zeros);
+    upload_mask(kc, zeros);
+    upload_mask(conv, zeros);
+    YQ_HIP(hipMemcpyAsync(scale.p, sc.data(), nc * sizeof(double), hipMemcpyHostToDevice, stream));
+    YQ_HIP(hipMemcpyAsync(gv.p, g0.data(), g0.size() * sizeof(double), hipMemcpyHostToDevice, stream));
+    YQ_HIP(hipMemcpyAsync(bnorm.p, bnv.data(), nc * sizeof(double), hipMemcpyHostToDevice, stream));
+    YQ_HIP(hipMemcpyAsync(rtol.p, rt.data(), nc * sizeof(double), hipMemcpyHostToDevice, stream));
+    // V0 = r / beta
+    bscale_kernel<<<nb256(T), 256, 0, stream>>>(node_conf.p, T, active.p, jc.p, scale.p, r.p, V.p);
+    YQ_HIP(hipGetLastError());
+    // iterate: at most m steps; the mask retires converged configurations
+    int left = nact;
+    for (int step = 0; step < m && left > 0; step += 2) {
+      run_iteration(prec);
+      if (step + 1 < m) run_iteration(prec);
+      left = count_active(hact);
+    }
+    // cycle end: y = H^-1 g and x += V y for the cycle's participants
+    upload_mask(inc, act);
+    bsolve_kernel<<<nb256(nc), 256, 0, stream>>>(nc, m, inc.p, kc.p, H.p, gv.p, yv.p);
+    bupdate_kernel<<<nb256(T), 256, 0, stream>>>(node_conf.p, T, inc.p, nullptr, kc.p, V.p, yv.p, m,
+                                                 0, 1.0, x);
+    YQ_HIP(hipGetLastError());
+    std::vector<int> hk(nc), hc(nc);
+    YQ_HIP(hipMemcpyAsync(hk.data(), kc.p, nc * sizeof(int), hipMemcpyDeviceToHost, stream));
+    YQ_HIP(hipMemcpyAsync(hc.data(), conv.p, nc * sizeof(int), hipMemcpyDeviceToHost, stream));
+    YQ_HIP(hipStreamSynchronize(stream));
+    for (int c = 0; c < nc; ++c) {
+      if (!act[c]) continue;
+      iters[c] += hk[c];
+      budget[c] -= hk[c];
+      if (hc[c]) {
+        converged[c] = 1;
+        part[c] = 0;
+      } else if (budget[c] <= 0) {
+        part[c] = 0;
+      }
+    }
+    int any = 0;
+    for (int c = 0; c < nc; ++c) any += part[c];
+    if (!any) break;
+  }
+}
+
+// Full solve (FP64 or mixed with refinement) of every member; results in x.
+void Engine::solve(std::vector<yq_solve_info>& info, double* x_out) {
+  const int nc = (int)members.size();
+  auto t0 = std::chrono::steady_clock::now();
+  info.assign(nc, yq_solve_info{});
+  std::vector<int> all(nc, 1), iters(nc, 0), budget(nc, prm.maxiter), conv_c(nc, 0);
+  for (int c = 0; c < nc; ++c) all[c] = members[c].pb ? 1 : 0;
+  int mv = 0;
+  upload_mask(inc, all);
+  dots(inc.p, f.p, f.p);
+  std::vector<double> fn = read_nrm();
+  for (double& v : fn) v = std::sqrt(std::max(v, 0.0));
+  if (prm.precision == YQ_FP64) {
+    std::vector<double> tolv(nc, prm.tol);
+    gmres(YQ_FP64, f.p, x_out, all, tolv, iters, budget, conv_c, mv);
+    for (int c = 0; c < nc; ++c) {
+      info[c].iterations = iters[c];
+      info[c].matvecs_fp64 = iters[c];
+      info[c].outer_steps = 1;
+    }
+  } else {
+    std::vector<int> run(all), dummy;
+    axpby(inc.p, 0.0, f.p, 0.0, nullptr, x_out);
+    for (int outer = 0; outer < prm.max_refine; ++outer) {
+      std::vector<double> rel(nc, 1.0);
+      upload_mask(inc, run);
+      if (outer == 0) {
+        axpby(inc.p, 1.0, f.p, 0.0, nullptr, r.p);
+      } else {
+        matvec(YQ_FP64, inc.p, x_out, nullptr, tmp.p);
+        axpby(inc.p, 1.0, f.p, -1.0, tmp.p, r.p);
+        for (int c = 0; c < nc; ++c)
+          if (run[c]) ++info[c].matvecs_fp64;
+        dots(inc.p, r.p, r.p);
+        std::vector<double> rn = read_nrm();
+        for (int c = 0; c < nc; ++c)
+          if (run[c]) rel[c] = fn[c] > 0.0 ? std::sqrt(std::max(rn[c], 0.0)) / fn[c] : 0.0;
+      }
+      int nrun = 0;
+      std::vector<double> tolv(nc, 0.5);
+      for (int c = 0; c < nc; ++c) {
+        if (!run[c]) continue;
+        if (rel[c] <= prm.tol || budget[c] <= 0) {
+          run[c] = 0;
+          continue;
+        }
+        ++nrun;
+        ++info[c].outer_steps;
+        tolv[c] = std::min(0.5, std::max(prm.inner_tol, 0.5 * prm.tol / std::max(rel[c], 1e-300)));
+      }
+      if (!nrun) break;
+      // the residual r is the right-hand side of the inner solve; delta -> x
+      std::vector<int> it0(nc, 0);
+      gmres(YQ_MIXED, r.p, delta.p, run, tolv, it0, budget, conv_c, mv);
+      for (int c = 0; c < nc; ++c)
+        if (run[c]) {
+          iters[c] += it0[c];
+          info[c].matvecs_fp32 += it0[c];
+        }
+      upload_mask(inc, run);
+      axpby(inc.p, 1.0, delta.p, 1.0, x_out, x_out);
+    }
+    for (int c = 0; c < nc; ++c) info[c].iterations = iters[c];
+  }
+  // true FP64 residual of every member
+  upload_mask(inc, all);
+  matvec(YQ_FP64, inc.p, x_out, nullptr, tmp.p);
+  axpby(inc.p, 1.0, f.p, -1.0, tmp.p, r.p);
+  dots(inc.p, r.p, r.p);
+  std::vector<double> rn = read_nrm();
+  const double sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  for (int c = 0; c < nc; ++c) {
+    info[c].residual = fn[c] > 0.0 ? std::sqrt(std::max(rn[c], 0.0)) / fn[c] : 0.0;
+    info[c].matvecs_fp64 += 1;
+    info[c].seconds = sec;
+  }
+}
+
+}  // namespace yq

@@ -122,7 +122,7 @@ struct FarPlan {
   int chunks;    // source chunks
   int chunk;     // sources per chunk (multiple of the block size)
 };
-FarPlan far_plan(int64_t nt, int64_t ns, int block);
+FarPlan far_plan(int64_t nt, int64_t ns, int block, int want = 4096);
 void launch_far64(const GeomView& g, const double* sigma, const FarPlan& fp, double* partial,
                   hipStream_t s);
 void launch_far32(const double* x, const double* y, const float* wnx, const float* wny,

@@ -13,15 +13,17 @@
 // fixed order (deterministic), scales, and applies the near correction.
 #include "bessel.h"
 #include "common.h"
+#include "farfield_core.h"
 
 namespace yq {
 
 constexpr int FAR_BS = 256;
 
-FarPlan far_plan(int64_t nt, int64_t ns, int block) {
+// Source chunks are chosen so that one configuration alone gives about `want`
+// blocks (>= 16 per compute unit at 4096); the plan depends only on the sizes.
+FarPlan far_plan(int64_t nt, int64_t ns, int block, int want) {
   FarPlan fp;
   fp.tblocks = (int)((nt + block - 1) / block);
-  const int want = 4096;  // >= 16 blocks per compute unit
   int64_t src_tiles = (ns + block - 1) / block;
   int64_t chunks = (want + fp.tblocks - 1) / fp.tblocks;
   if (chunks > src_tiles) chunks = src_tiles;
@@ -55,14 +57,7 @@ __global__ __launch_bounds__(FAR_BS) void far64_kernel(GeomView g, const double*
     }
     __syncthreads();
     const int nb = (int)min((int64_t)FAR_BS, j1 - jb);
-    for (int k = 0; k < nb; ++k) {
-      const double2 p = sxy[k];
-      const double2 q = sq[k];
-      const double dx = xi - p.x, dy = yi - p.y;
-      const double r2 = fma(dx, dx, dy * dy);
-      const double v = k1z_64(kap2 * r2, g.tab) * fma(dx, q.x, dy * q.y);
-      acc += r2 > 0.0 ? v : 0.0;
-    }
+    acc = far64_tile(xi, yi, sxy, sq, nb, kap2, g.tab, acc);
   }
   if (i < N) partial[(int64_t)blockIdx.y * N + i] = acc;
 }
@@ -97,13 +92,7 @@ __global__ __launch_bounds__(FAR_BS) void far32_kernel(const double* __restrict_
     }
     __syncthreads();
     const int nb = (int)min((int64_t)FAR_BS, j1 - jb);
-    for (int k = 0; k < nb; ++k) {
-      const double2 p = sxy[k];
-      const float2 q = sq[k];
-      const float dx = (float)(xi - p.x), dy = (float)(yi - p.y);
-      const float z2 = fmaxf(kap2 * fmaf(dx, dx, dy * dy), 1e-30f);
-      acc = fmaf(k1z_32(z2), fmaf(dx, q.x, dy * q.y), acc);
-    }
+    acc = far32_tile(xi, yi, sxy, sq, nb, kap2, acc);
   }
   if (i < N) partial[(int64_t)blockIdx.y * N + i] = acc;
 }
@@ -171,24 +160,7 @@ __global__ void finish_kernel(GeomView g, int win, int chunks, const double* __r
     for (int c = 0; c < chunks; ++c) s += (double)p32[(int64_t)c * N + i];
   }
   s *= g.kappa * g.kappa / (2.0 * PI);
-  const int P = g.P;
-  const int64_t pan = i / Q;
-  const int64_t pid = pan / P;
-  const int k = (int)(pan % P);
-  double corr = 0.0;
-  for (int sl = 0; sl <= 2 * win; ++sl) {
-    int kj = (k + sl - win) % P;
-    if (kj < 0) kj += P;
-    const double* sg = sigma + (pid * P + kj) * Q;
-    const double* wr = W + (int64_t)sl * Q * N + i;
-#pragma unroll
-    for (int m = 0; m < Q; ++m) corr = fma(wr[(int64_t)m * N], sg[m], corr);
-  }
-  if (xvals) for (int e = xrow[i]; e < xrow[i + 1]; ++e) {
-    const double* sg = sigma + (int64_t)xpan[e] * Q;
-    const double* vr = xvals + (int64_t)e * Q;
-    for (int m = 0; m < Q; ++m) corr = fma(vr[m], sg[m], corr);
-  }
+  const double corr = win < 0 ? 0.0 : correction_row(i, N, g.P, win, W, xrow, xpan, xvals, sigma);
   out[i] = s + corr;
 }
 

@@ -1,0 +1,87 @@
+// Internal definition of the problem handle (shared by api.hip and batch.hip).
+#pragma once
+
+#include <utility>
+#include <vector>
+
+#include "common.h"
+
+using namespace yq;
+
+struct yq_problem {
+  yq_params prm{};
+  hipStream_t stream = nullptr;
+  std::string err;
+
+  int n = 0;
+  int64_t N = 0;
+  double kappa = 0.0;
+  bool ready = false;
+  bool have_f = false;
+  bool batch_member = false;  // workspace for GMRES/forces comes from the batch
+  int far_want = 4096;        // far-field plan parameter (far_plan)
+
+  std::vector<double> h_pc;  // [n*5]
+  DevBuf<double> pc, x, y, nx, ny, w, wnx, wny, panel_h, pcx, pcy, pr;
+  DevBuf<float> wnx32, wny32;
+  DevBuf<double> pot_partial;
+  DevBuf<int> nb_ptr, nb_idx, bad;
+  DevBuf<int> xrow, xpan;
+  int64_t x_total = 0;
+  DevBuf<double> xvals, xgvals;
+  DevBuf<double> W, WGx, WGy;
+  DevBuf<double> Lqbx, Lnear, Lpot, tab;
+  Consts consts{};
+  FarPlan fp{};
+  DevBuf<double> partial, gpartial;
+  DevBuf<float> partial32;
+  DevBuf<double> f;
+  // Krylov workspace
+  DevBuf<double> V, kw, kr, kd, kpart, kred;
+  DevBuf<double> gx, gy, en;
+
+  // per-phase timers
+  static constexpr int NPHASE = 6;
+  bool prof = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[NPHASE];
+  std::vector<hipEvent_t> pool;
+
+  hipEvent_t event() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e;
+    YQ_HIP(hipEventCreate(&e));
+    return e;
+  }
+  ~yq_problem() {
+    for (auto& v : ev)
+      for (auto& p : v) {
+        (void)hipEventDestroy(p.first);
+        (void)hipEventDestroy(p.second);
+      }
+    for (auto e : pool) (void)hipEventDestroy(e);
+  }
+
+  GeomView view() const {
+    GeomView g;
+    g.n = n;
+    g.P = prm.panels_per_particle;
+    g.N = N;
+    g.kappa = kappa;
+    g.pc = pc.p;
+    g.x = x.p;
+    g.y = y.p;
+    g.nx = nx.p;
+    g.ny = ny.p;
+    g.w = w.p;
+    g.wnx = wnx.p;
+    g.wny = wny.p;
+    g.panel_h = panel_h.p;
+    g.tab = tab.p;
+    return g;
+  }
+};
+

@@ -1,0 +1,161 @@
+"""Batched solves (many configurations per fused launch) against the oracle, against
+the single-configuration path, and alone vs in a mix."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from oracle.geometry import Params
+
+pytestmark = pytest.mark.gpu
+
+yq = pytest.importorskip("paper_1810_04131_amd")
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _rel(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+P, ORDER = 12, 8
+
+
+def _configs():
+    # uneven sizes and screening constants; one config with a ragged node count
+    return [
+        workloads.random_ellipses(3, 9.0, 0.7, seed=1),
+        workloads.two_ellipses(2, 1.6),
+        workloads.random_ellipses(5, 12.0, 1.2, seed=3),
+        workloads.single_disk(1.0, 0.5),
+    ]
+
+
+@pytest.fixture(scope="module")
+def oracles():
+    out = []
+    for c in _configs():
+        d = oracle.discretize(c, Params(panels=P, qbx_order=ORDER))
+        A = oracle.build_matrices(d)
+        f = oracle.arc_label(d)
+        out.append(dict(d=d, A=A, f=f, sigma=oracle.lu_solve(A, f)))
+    return out
+
+
+def _batch(configs, **kw):
+    _torch()
+    b = yq.Batch(yq.default_params(panels_per_particle=P, qbx_order=ORDER, **kw))
+    b.set_configs(configs)
+    return b
+
+
+def test_batch_operator_parity(oracles):
+    b = _batch(_configs())
+    sig = np.concatenate([workloads.random_density(o["d"].N, 7 + c) for c, o in enumerate(oracles)])
+    out = _np(b.apply_operator(sig))
+    out32 = _np(b.apply_operator(sig, yq.YQ_MIXED))
+    for c, o in enumerate(oracles):
+        s = slice(int(b.offsets[c]), int(b.offsets[c + 1]))
+        ref = o["A"] @ sig[s]
+        assert _rel(out[s], ref) < 1e-12, c
+        assert _rel(out32[s], ref) < 5e-6, c
+
+
+@pytest.mark.parametrize("precision,tol,bound", [(0, 1e-13, 1e-10), (1, 1e-9, 1e-8)])
+def test_batch_solve_parity(oracles, precision, tol, bound):
+    b = _batch(_configs(), tol=tol, precision=precision)
+    f = b.boundary_label()
+    b.set_boundary_data(f)
+    sig, infos = b.solve()
+    sig = _np(sig)
+    for c, o in enumerate(oracles):
+        s = slice(int(b.offsets[c]), int(b.offsets[c + 1]))
+        assert _rel(_np(f)[s], o["f"]) < 1e-13
+        assert infos[c]["residual"] <= tol, (c, infos[c])
+        assert _rel(sig[s], o["sigma"]) < bound, c
+
+
+def test_batch_alone_equals_mix_and_single_path():
+    torch = _torch()
+    cfgs = _configs()
+    mix = _batch(cfgs, tol=1e-10, precision=1)
+    mix.set_boundary_data(mix.boundary_label())
+    sm, im = mix.solve()
+    sm = _np(sm)
+    for c, cfg in enumerate(cfgs):
+        alone = _batch([cfg], tol=1e-10, precision=1)
+        alone.set_boundary_data(alone.boundary_label())
+        sa, ia = alone.solve()
+        seg = sm[int(mix.offsets[c]):int(mix.offsets[c + 1])]
+        # same arithmetic for a configuration alone and in the mix: bitwise equal
+        assert np.array_equal(_np(sa), seg), c
+        assert ia[0]["iterations"] == im[c]["iterations"]
+        # and the single-problem path agrees within the solve tolerance
+        pb = yq.Problem(yq.default_params(panels_per_particle=P, qbx_order=ORDER, tol=1e-10,
+                                          precision=1))
+        pb.set_workload(cfg)
+        pb.set_boundary_data(pb.boundary_label())
+        ss, _ = pb.solve()
+        assert _rel(_np(ss), seg) < 1e-8
+
+
+def test_batch_graph_replays_match_eager():
+    torch = _torch()
+    cfgs = _configs()
+    g = _batch(cfgs, tol=1e-10, precision=1)
+    e = _batch(cfgs, tol=1e-10, precision=1)
+    e.use_graphs(False)
+    for b in (g, e):
+        b.set_boundary_data(b.boundary_label())
+    se, _ = e.solve()
+    se = _np(se)
+    sig = np.random.default_rng(0).standard_normal(g.total)
+    for rep in range(3):
+        sg, _ = g.solve()              # every iteration is a graph replay
+        assert np.array_equal(_np(sg), se), rep
+        # eager work and synchronisation between replays
+        o1 = _np(g.apply_operator(sig))
+        o2 = _np(e.apply_operator(sig))
+        assert np.array_equal(o1, o2)
+        torch.cuda.synchronize()
+
+
+def test_batch_forces_match_single():
+    torch = _torch()
+    cfgs = _configs()
+    b = _batch(cfgs, tol=1e-10)
+    b.set_boundary_data(b.boundary_label())
+    sig, _ = b.solve()
+    F, T, E = b.forces(sig)
+    F, T = _np(F), _np(T)
+    p0 = 0
+    for c, cfg in enumerate(cfgs):
+        pb = yq.Problem(yq.default_params(panels_per_particle=P, qbx_order=ORDER))
+        pb.set_workload(cfg)
+        pb.set_boundary_data(pb.boundary_label())
+        Fs, Ts, Es = pb.forces(b.segment(sig, c))
+        n = cfg.center.shape[0]
+        assert np.array_equal(_np(Fs), F[p0:p0 + n]) and np.array_equal(_np(Ts), T[p0:p0 + n])
+        assert Es == E[c]
+        p0 += n
+
+
+def test_batch_autotune_keeps_results_within_tolerance(oracles):
+    b = _batch(_configs(), tol=1e-10, precision=1)
+    pbk, fw = b.autotune()
+    assert pbk in (1024, 2048, 4096, 8192) and fw in (2048, 4096, 8192)
+    b.set_boundary_data(b.boundary_label())
+    sig, infos = b.solve()
+    sig = _np(sig)
+    for c, o in enumerate(oracles):
+        s = slice(int(b.offsets[c]), int(b.offsets[c + 1]))
+        assert _rel(sig[s], o["sigma"]) < 1e-8
