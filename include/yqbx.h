@@ -224,6 +224,51 @@ int yq_batch_autotune(yq_batch* batch, int32_t* persist_blocks, int32_t* far_wan
 /* enable != 0: replay the captured iteration graph (default); 0: launch eagerly. */
 int yq_batch_use_graphs(yq_batch* batch, int32_t enable);
 
+/* ---- Serving (step a14) ------------------------------------------------------------------
+ * A continuous-batching solve server on one GPU.  Requests (one particle
+ * configuration each) are queued by yq_server_submit and advanced by
+ * yq_server_step, one scheduling tick per call:
+ *   admission (arrival order, first fit) while a free range of the node arena
+ *   (node_capacity nodes) and the device-memory budget (mem_budget_bytes, by a
+ *   per-request estimate) allow, at most max_slots requests at once; then an
+ *   FP64 residual for requests between refinement steps, one Arnoldi step of the
+ *   fused batch iteration for every request inside a GMRES cycle, cycle ends,
+ *   and finished requests (forces with gamma = 1, results copied to the host,
+ *   resources released).
+ * Work of requests in flight shares every fused launch; a request's arithmetic
+ * depends only on its own size, so its result is the same alone or in a mix.
+ * Latency = completion time - submit time (steady clock).  The server owns a
+ * HIP stream of default priority; calls are synchronous. */
+typedef struct yq_server yq_server;
+
+int yq_server_create(const yq_params* params, int64_t node_capacity, int32_t max_slots,
+                     double mem_budget_bytes, yq_server** out);
+void yq_server_destroy(yq_server* server);
+const char* yq_server_last_error(const yq_server* server);
+
+/* Queues a request (host arrays copied; label as yq_boundary_label).  ticket:
+ * host out.  YQ_EADMIT (ticket still set, state failed) if the request can
+ * never fit the node capacity or the memory budget. */
+int yq_server_submit(yq_server* server, int32_t n, const double* center_xy, const double* angle,
+                     const double* semi_axes, double kappa, int32_t label_kind, double param0,
+                     double param1, int64_t* ticket);
+
+/* One tick.  completed / running / queued: host out (may be NULL). */
+int yq_server_step(yq_server* server, int32_t* completed, int32_t* running, int32_t* queued);
+
+/* state: 0 queued, 1 running, 2 done, 3 failed.  For done/failed requests the
+ * host outputs (each may be NULL) receive sigma [N], force [2n], torque [n],
+ * energy, info and the latency in seconds. */
+int yq_server_result(yq_server* server, int64_t ticket, int32_t* state, int64_t* N, int32_t* n,
+                     double* sigma, double* force, double* torque, double* energy,
+                     yq_solve_info* info, double* latency_s);
+
+/* Forgets a finished request's stored results. */
+int yq_server_release(yq_server* server, int64_t ticket);
+
+/* Removes a queued or running request (it ends in state failed, "cancelled"). */
+int yq_server_cancel(yq_server* server, int64_t ticket);
+
 /* Per-phase GPU timers: with profiling enabled every launch of a phase is
  * bracketed by hipEvents on the problem's stream.  Phases: 0 FP64 far field,
  * 1 FP32 far field, 2 finish (chunk sum + near correction), 3 gradient far

@@ -14,7 +14,7 @@ from . import _lib
 from ._lib import (YQ_FAR_AUTO, YQ_FAR_DIRECT, YQ_FAR_FMM, YQ_FP64, YQ_LABEL_ARC,  # noqa: F401
                    YQ_LABEL_JANUS, YQ_MIXED, YQError, yq_params, yq_solve_info)
 
-__all__ = ["Problem", "Batch", "default_params", "bessel", "YQError", "YQ_FP64", "YQ_MIXED"]
+__all__ = ["Problem", "Batch", "Server", "default_params", "bessel", "YQError", "YQ_FP64", "YQ_MIXED"]
 
 
 def _torch():
@@ -283,6 +283,94 @@ class Batch:
 
     def segment(self, v, c):
         return v[int(self.offsets[c]):int(self.offsets[c + 1])]
+
+
+class Server:
+    """Continuous-batching solve server (a yq_server handle); see include/yqbx.h."""
+
+    QUEUED, RUNNING, DONE, FAILED = 0, 1, 2, 3
+
+    def __init__(self, params: Optional[yq_params] = None, node_capacity=1 << 20, max_slots=64,
+                 mem_budget_bytes=64e9, device: str = "cuda:0", **overrides):
+        torch = _torch()
+        torch.cuda.set_device(torch.device(device))
+        self.lib = _lib.load()
+        self.params = params if params is not None else default_params(**overrides)
+        h = ctypes.c_void_p()
+        _lib.check(self.lib.yq_server_create(ctypes.byref(self.params), int(node_capacity),
+                                             int(max_slots), float(mem_budget_bytes),
+                                             ctypes.byref(h)), None, server=True)
+        self.h = h
+        self.sizes = {}
+
+    def _check(self, st):
+        return _lib.check(st, self.h, server=True)
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            self.lib.yq_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, particles, label_kind=YQ_LABEL_ARC, a=0.7853981633974483, b=0.1):
+        import numpy as np
+        c = np.ascontiguousarray(np.asarray(particles.center, float).reshape(-1))
+        an = np.ascontiguousarray(np.asarray(particles.angle, float).reshape(-1))
+        ax = np.ascontiguousarray(np.asarray(particles.axes, float).reshape(-1))
+        t = ctypes.c_int64()
+        vp = lambda x: x.ctypes.data_as(ctypes.c_void_p)
+        self._check(self.lib.yq_server_submit(self.h, an.size, vp(c), vp(an), vp(ax),
+                                              float(particles.kappa), label_kind, float(a),
+                                              float(b), ctypes.byref(t)))
+        return int(t.value)
+
+    def step(self):
+        c, r, q = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        self._check(self.lib.yq_server_step(self.h, ctypes.byref(c), ctypes.byref(r), ctypes.byref(q)))
+        return int(c.value), int(r.value), int(q.value)
+
+    def state(self, ticket):
+        st, N, n = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int32()
+        self._check(self.lib.yq_server_result(self.h, ticket, ctypes.byref(st), ctypes.byref(N),
+                                              ctypes.byref(n), None, None, None, None, None, None))
+        return int(st.value), int(N.value), int(n.value)
+
+    def result(self, ticket):
+        import numpy as np
+        st, N, n = self.state(ticket)
+        if st not in (self.DONE, self.FAILED):
+            return None
+        sig = np.zeros(N)
+        F = np.zeros(2 * n)
+        T = np.zeros(n)
+        e = ctypes.c_double()
+        info = yq_solve_info()
+        lat = ctypes.c_double()
+        stc, Nc, nc = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int32()
+        vp = lambda x: x.ctypes.data_as(ctypes.c_void_p)
+        self._check(self.lib.yq_server_result(self.h, ticket, ctypes.byref(stc), ctypes.byref(Nc),
+                                              ctypes.byref(nc), vp(sig), vp(F), vp(T),
+                                              ctypes.byref(e), ctypes.byref(info), ctypes.byref(lat)))
+        return dict(state=st, sigma=sig, force=F.reshape(n, 2), torque=T, energy=e.value,
+                    info={k: getattr(info, k) for k, _ in info._fields_}, latency=lat.value)
+
+    def release(self, ticket):
+        self._check(self.lib.yq_server_release(self.h, ticket))
+
+    def cancel(self, ticket):
+        self._check(self.lib.yq_server_cancel(self.h, ticket))
+
+    def run_until_idle(self, max_ticks=100000):
+        for _ in range(max_ticks):
+            c, r, q = self.step()
+            if r == 0 and q == 0:
+                return
+        raise RuntimeError("server did not drain")
 
 
 def bessel(kind, order, z, precision=YQ_FP64):

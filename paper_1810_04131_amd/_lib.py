@@ -100,6 +100,19 @@ SIGNATURES = {
     "yq_batch_forces": (c_int32, [P, P, c_double, P, P, P]),
     "yq_batch_autotune": (c_int32, [P, ctypes.POINTER(c_int32), ctypes.POINTER(c_int32)]),
     "yq_batch_use_graphs": (c_int32, [P, c_int32]),
+    "yq_server_create": (c_int32, [ctypes.POINTER(yq_params), c_int64, c_int32, c_double,
+                                   ctypes.POINTER(c_void_p)]),
+    "yq_server_destroy": (None, [P]),
+    "yq_server_last_error": (c_char_p, [P]),
+    "yq_server_submit": (c_int32, [P, c_int32, P, P, P, c_double, c_int32, c_double, c_double,
+                                   ctypes.POINTER(c_int64)]),
+    "yq_server_step": (c_int32, [P, ctypes.POINTER(c_int32), ctypes.POINTER(c_int32),
+                                 ctypes.POINTER(c_int32)]),
+    "yq_server_result": (c_int32, [P, c_int64, ctypes.POINTER(c_int32), ctypes.POINTER(c_int64),
+                                   ctypes.POINTER(c_int32), P, P, P, ctypes.POINTER(c_double),
+                                   ctypes.POINTER(yq_solve_info), ctypes.POINTER(c_double)]),
+    "yq_server_release": (c_int32, [P, c_int64]),
+    "yq_server_cancel": (c_int32, [P, c_int64]),
     "yq_profile_enable": (c_int32, [P, c_int32]),
     "yq_profile_read": (c_int32, [P, c_int32, ctypes.POINTER(c_int64), ctypes.POINTER(c_double),
                                   c_int32]),
@@ -130,11 +143,16 @@ def load():
     return lib
 
 
-def check(status, handle=None, batch=False):
+def check(status, handle=None, batch=False, server=False):
     if status == YQ_OK:
         return status
     lib = load()
-    detail = lib.yq_batch_last_error(handle) if batch else lib.yq_last_error(handle)
+    if server:
+        detail = lib.yq_server_last_error(handle)
+    elif batch:
+        detail = lib.yq_batch_last_error(handle)
+    else:
+        detail = lib.yq_last_error(handle)
     detail = detail.decode() if detail else ""
     base = lib.yq_error_string(status).decode()
     raise YQError(status, f"{base}: {detail}")

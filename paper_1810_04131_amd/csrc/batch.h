@@ -69,6 +69,8 @@ struct Engine {
   void iteration(int prec);
   void run_iteration(int prec);
   int count_active(std::vector<int>& h);
+  void solve_cycle(const int* mask, double* x);
+  void clear_active(const int* mask);
   std::vector<double> read_nrm();
   void upload_mask(DevBuf<int>& d, const std::vector<int>& h);
   void gmres(int prec, const double* b, double* x, const std::vector<int>& incl,

@@ -295,6 +295,11 @@ __global__ void baxpby_kernel(const int* __restrict__ node_conf, int64_t T,
   out[g] = a * x[g] + (y ? b * y[g] : 0.0);
 }
 
+__global__ void fill_int_kernel(int* __restrict__ p, int64_t n, int v) {
+  const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (g < n) p[g] = v;
+}
+
 static inline unsigned nb256(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 // ---- host engine -----------------------------------------------------------------------------
@@ -320,7 +325,6 @@ void Engine::rebuild() {
   std::vector<ConfDev> h(nc);
   std::vector<int4> it;
   std::vector<int2> kb;
-  std::vector<int> nconf_of((size_t)T, -1);
   int64_t kpoff = 0;
   for (int c = 0; c < nc; ++c) {
     Member& mb = members[c];
@@ -356,7 +360,6 @@ void Engine::rebuild() {
       for (int t = 0; t < d.tblocks; ++t)
         for (int s = 0; s < d.chunks; ++s) it.push_back(make_int4(c, t, s, 0));
       for (int b = 0; b < d.kb; ++b) kb.push_back(make_int2(c, b));
-      for (int64_t i = 0; i < d.N; ++i) nconf_of[mb.off + i] = c;
     }
   }
   nitems = (int)it.size();
@@ -369,9 +372,19 @@ void Engine::rebuild() {
   if (nc) YQ_HIP(hipMemcpyAsync(conf.p, h.data(), nc * sizeof(ConfDev), hipMemcpyHostToDevice, stream));
   if (nitems) YQ_HIP(hipMemcpyAsync(items.p, it.data(), nitems * sizeof(int4), hipMemcpyHostToDevice, stream));
   if (nkblk) YQ_HIP(hipMemcpyAsync(kblk.p, kb.data(), nkblk * sizeof(int2), hipMemcpyHostToDevice, stream));
-  if (T) YQ_HIP(hipMemcpyAsync(node_conf.p, nconf_of.data(), T * sizeof(int), hipMemcpyHostToDevice, stream));
-  // per-configuration state
+  // node -> configuration map (-1 on free arena ranges)
+  if (T) {
+    fill_int_kernel<<<nb256(T), 256, 0, stream>>>(node_conf.p, T, -1);
+    for (int c = 0; c < nc; ++c)
+      if (members[c].pb && members[c].pb->N > 0)
+        fill_int_kernel<<<nb256(members[c].pb->N), 256, 0, stream>>>(node_conf.p + members[c].off,
+                                                                   members[c].pb->N, c);
+    YQ_HIP(hipGetLastError());
+  }
+  // per-configuration state; flags start at zero when (re)allocated and are
+  // otherwise kept, so configurations in the middle of a cycle survive a rebuild
   const int hs = 2 * (m + 1) + 2;
+  const bool fresh = active.n != (size_t)std::max(nc, 1);
   active.alloc(std::max(nc, 1));
   inc.alloc(std::max(nc, 1));
   jc.alloc(std::max(nc, 1));
@@ -388,6 +401,13 @@ void Engine::rebuild() {
   rtol.alloc(std::max(nc, 1));
   res.alloc(std::max(nc, 1));
   nrm.alloc(std::max(nc, 1));
+  if (fresh) {
+    fill_int_kernel<<<nb256(std::max(nc, 1)), 256, 0, stream>>>(active.p, std::max(nc, 1), 0);
+    fill_int_kernel<<<nb256(std::max(nc, 1)), 256, 0, stream>>>(kc.p, std::max(nc, 1), 0);
+    fill_int_kernel<<<nb256(std::max(nc, 1)), 256, 0, stream>>>(jc.p, std::max(nc, 1), 0);
+    fill_int_kernel<<<nb256(std::max(nc, 1)), 256, 0, stream>>>(conv.p, std::max(nc, 1), 0);
+    YQ_HIP(hipGetLastError());
+  }
   V.reserve((size_t)(m + 1) * std::max<int64_t>(T, 1));
   w.reserve(std::max<int64_t>(T, 1));
   r.reserve(std::max<int64_t>(T, 1));
@@ -475,6 +495,26 @@ void Engine::run_iteration(int prec) {
     YQ_HIP(hipGraphDestroy(graph));
   }
   YQ_HIP(hipGraphLaunch(graph_exec[gi], stream));
+}
+
+// y = H^-1 g and x += V y for the masked configurations' finished cycles.
+void Engine::solve_cycle(const int* mask, double* x) {
+  const int nc = (int)members.size();
+  bsolve_kernel<<<nb256(nc), 256, 0, stream>>>(nc, m, mask, kc.p, H.p, gv.p, yv.p);
+  bupdate_kernel<<<nb256(T), 256, 0, stream>>>(node_conf.p, T, mask, nullptr, kc.p, V.p, yv.p, m,
+                                               0, 1.0, x);
+  YQ_HIP(hipGetLastError());
+}
+
+__global__ void clear_kernel(int n, const int* __restrict__ mask, int* __restrict__ active) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < n && mask[c]) active[c] = 0;
+}
+
+void Engine::clear_active(const int* mask) {
+  const int nc = (int)members.size();
+  clear_kernel<<<nb256(nc), 256, 0, stream>>>(nc, mask, active.p);
+  YQ_HIP(hipGetLastError());
 }
 
 int Engine::count_active(std::vector<int>& h) {
