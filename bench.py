@@ -57,6 +57,15 @@ def parse():
     ap.add_argument("--fp64-steps", type=int, default=3)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy (counter calibration)")
+    ap.add_argument("--workload", choices=["medium", "batch", "serve"], default="medium",
+                    help="medium: the 50-ellipse solve (default line); batch: many configurations "
+                         "per fused launch; serve: Poisson-arrival continuous batching")
+    ap.add_argument("--configs", type=int, default=128, help="batch: number of configurations")
+    ap.add_argument("--requests", type=int, default=96, help="serve: number of requests")
+    ap.add_argument("--rate", type=float, default=40.0, help="serve: arrival rate (1/s)")
+    ap.add_argument("--nmax", type=int, default=200, help="batch/serve: largest particle count")
+    ap.add_argument("--single-baseline", type=int, default=100000,
+                    help="batch: configurations also solved one at a time for comparison")
     return ap.parse_args()
 
 
@@ -146,11 +155,166 @@ def cpu_baseline(cfg, rows):
                        f"numpy/scipy, {dt:.1f} s")
 
 
+def bench_batch(args):
+    """Many configurations per fused launch (log-uniform 10..nmax ellipses each)."""
+    import numpy as np
+    import torch
+
+    import paper_1810_04131_amd as yq
+    import workloads
+    cfgs = workloads.batched_configs(args.configs, seed=0, nmax=args.nmax)
+    prm = yq.default_params(panels_per_particle=32, qbx_order=10, tol=1e-8,
+                            precision=yq.YQ_MIXED, restart=60, maxiter=300)
+    b = yq.Batch(prm)
+    t0 = time.perf_counter()
+    b.set_configs(cfgs)
+    t_setup = time.perf_counter() - t0
+    pblk, fwant = b.autotune()
+    b.set_boundary_data(b.boundary_label())
+    b.solve()                                   # warm-up (captures the iteration graph)
+    lat = []
+    for _ in range(max(args.steps, 1)):
+        t0 = time.perf_counter()
+        sig, infos = b.solve()
+        lat.append(time.perf_counter() - t0)
+    F, T, E = b.forces(sig)
+    torch.cuda.synchronize()
+    N = np.diff(b.offsets).astype(float)
+    its = np.array([i["iterations"] for i in infos])
+    ref = np.array([i["outer_steps"] for i in infos])
+    resid = max(i["residual"] for i in infos)
+    # one fused FP32 far-field pass evaluates sum_c N_c^2 pairs; time it alone
+    s = torch.randn(b.total, dtype=torch.float64, device="cuda")
+    b.apply_operator(s, yq.YQ_MIXED)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        b.apply_operator(s, yq.YQ_MIXED)
+    torch.cuda.synchronize()
+    t_mv = (time.perf_counter() - t0) / 3
+    pairs = float((N * N).sum())
+    t_solve = percentile(lat, 0.5)
+    # one at a time, same solver, on the first configurations
+    k1 = min(args.single_baseline, len(cfgs))
+    t_single = 0.0
+    for c in cfgs[:k1]:
+        pb = yq.Problem(prm)
+        t0 = time.perf_counter()
+        pb.set_workload(c)
+        pb.set_boundary_data(pb.boundary_label())
+        pb.solve()
+        torch.cuda.synchronize()
+        t_single += time.perf_counter() - t0
+    out = {
+        "metric": "source-target interactions/s per matvec; solves/s + p50/p99 latency at 1e-8 rel err",
+        "value": pairs / t_mv, "unit": "interactions/s", "n_gpus": 1, "steps": len(lat),
+        "warmup": 1, "ms_per_step": t_solve * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": f"batched: {len(cfgs)} configurations of 10-{args.nmax} ellipses "
+                               f"(log-uniform), 32x16 nodes per particle, kappa~U[0.5,2], "
+                               f"QBX order 10, mixed FP32/FP64 to 1e-8",
+                   "configs": len(cfgs), "total_nodes": int(N.sum()),
+                   "parallelism": "single GPU"},
+        "solves_per_s": len(cfgs) / t_solve,
+        "batch_latency_ms_p50": t_solve * 1e3, "batch_latency_ms_p99": percentile(lat, 0.99) * 1e3,
+        "setup_s": t_setup, "autotune": {"persist_blocks": pblk, "far_want": fwant},
+        "fused_far32_pass_ms": t_mv * 1e3, "pairs_per_fused_pass": pairs,
+        "gmres_iterations_mean": float(its.mean()), "gmres_iterations_max": int(its.max()),
+        "refine_steps_max": int(ref.max()), "residual_max": resid,
+        "one_at_a_time_solves_per_s": k1 / t_single if t_single else None,
+        "one_at_a_time_sample": k1,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_serve(args):
+    """Poisson arrivals replayed in real time against the continuous-batching server,
+    and the FP64 one-at-a-time path on the same trace (FCFS)."""
+    import numpy as np
+    import torch
+
+    import paper_1810_04131_amd as yq
+    import workloads
+    trace = workloads.serving_trace(args.requests, rate=args.rate, seed=1, nmax=args.nmax)
+    parts = [workloads.trace_particles(r) for r in trace]
+    prm = yq.default_params(panels_per_particle=32, qbx_order=10, tol=1e-8, precision=yq.YQ_MIXED,
+                            restart=60, maxiter=300)
+    cap = int(max(p.n for p in parts) * 512 * 6)
+    srv = yq.Server(prm, node_capacity=cap, max_slots=48, mem_budget_bytes=150e9)
+    # warm-up request (graph capture, code paths)
+    w = srv.submit(parts[0])
+    srv.run_until_idle()
+    srv.release(w)
+    t0 = time.perf_counter()
+    pending = list(zip(trace, parts))
+    tickets = []
+    peak = 0
+    while True:
+        now = time.perf_counter() - t0
+        while pending and pending[0][0]["arrival"] <= now:
+            r, p = pending.pop(0)
+            tickets.append((r, srv.submit(p)))
+        c, run, q = srv.step()
+        peak = max(peak, run)
+        if run == 0 and q == 0:
+            if not pending:
+                break
+            time.sleep(max(0.0, min(0.002, pending[0][0]["arrival"] - now)))
+    wall = time.perf_counter() - t0
+    lat = []
+    worst = 0.0
+    for r, t in tickets:
+        res = srv.result(t)
+        lat.append(res["latency"])
+        worst = max(worst, res["info"]["residual"])
+    # FP64 one-at-a-time path: each request solved alone, first come first served
+    p64 = yq.default_params(panels_per_particle=32, qbx_order=10, tol=1e-8, precision=yq.YQ_FP64,
+                            restart=60, maxiter=300)
+    service = []
+    for p in parts:
+        pb = yq.Problem(p64)
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        pb.set_workload(p)
+        pb.set_boundary_data(pb.boundary_label())
+        s, _ = pb.solve()
+        pb.forces(s)
+        torch.cuda.synchronize()
+        service.append(time.perf_counter() - a)
+    tfree = 0.0
+    lat64 = []
+    for r, sv in zip(trace, service):
+        start = max(tfree, r["arrival"])
+        tfree = start + sv
+        lat64.append(tfree - r["arrival"])
+    out = {
+        "metric": "source-target interactions/s per matvec; solves/s + p50/p99 latency at 1e-8 rel err",
+        "value": len(tickets) / wall, "unit": "solves/s", "n_gpus": 1, "steps": len(tickets),
+        "warmup": 1, "ms_per_step": wall / max(len(tickets), 1) * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": f"serving: Poisson arrivals at {args.rate:g}/s, {len(tickets)} "
+                               f"requests of 10-{args.nmax} ellipses (log-uniform), kappa~U[0.5,2], "
+                               f"32x16 nodes per particle, QBX order 10, mixed FP32/FP64 to 1e-8",
+                   "parallelism": "single GPU"},
+        "latency_ms_p50": percentile(lat, 0.5) * 1e3, "latency_ms_p99": percentile(lat, 0.99) * 1e3,
+        "solves_per_s": len(tickets) / wall, "peak_concurrent": peak, "residual_max": worst,
+        "fp64_one_at_a_time": {"latency_ms_p50": percentile(lat64, 0.5) * 1e3,
+                               "latency_ms_p99": percentile(lat64, 0.99) * 1e3,
+                               "solves_per_s": len(service) / max(tfree, 1e-9),
+                               "mean_service_ms": float(np.mean(service)) * 1e3},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.copy_probe:
         copy_probe()
         return
+    if args.workload == "batch":
+        return bench_batch(args)
+    if args.workload == "serve":
+        return bench_serve(args)
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}))

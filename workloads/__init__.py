@@ -36,7 +36,7 @@ __all__ = [
     "random_density",
 ]
 
-_NSAMPLE = 256  # boundary samples per ellipse for the overlap test
+_NSAMPLE = 128  # boundary samples per ellipse for the overlap test
 
 
 @dataclasses.dataclass
@@ -97,6 +97,10 @@ def _place(rng, n, box, axes_fn, gap, max_tries=200000):
             A = np.asarray(axes)[:, 0]
             d = np.hypot(C[:, 0] - c[0], C[:, 1] - c[1])
             cand = np.nonzero(d < A + ax[0] + gap + 1e-6)[0]
+            B = np.asarray(axes)[:, 1]
+            if cand.size and np.any(d[cand] < B[cand] + ax[1] + gap):
+                ok = False      # the inscribed circles alone are closer than the gap
+                cand = cand[:0]
             if cand.size:
                 sp = _boundary_samples(c, th, ax)
                 for j in cand:
