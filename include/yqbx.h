@@ -53,6 +53,7 @@ enum {
 };
 
 enum { YQ_FP64 = 0, YQ_MIXED = 1 };                       /* precision */
+enum { YQ_FMM64 = 2 };  /* yq_apply_far only: FMM expansions with FP64 near interactions */
 enum { YQ_FAR_DIRECT = 0, YQ_FAR_FMM = 1, YQ_FAR_AUTO = 2 };   /* far-field mode */
 enum { YQ_LABEL_ARC = 0, YQ_LABEL_JANUS = 1 };             /* boundary labels */
 
@@ -139,8 +140,14 @@ int yq_boundary_label(yq_problem* prob, int32_t kind, double param0, double para
 int yq_set_boundary_data(yq_problem* prob, const double* f);
 
 /* Far field alone (step a5): out_i = sum_{j != i} w_j dG/dnu_y(x_i, y_j) sigma_j
- * over every node pair, in FP64 (YQ_FP64) or FP32 arithmetic (YQ_MIXED).
- * dev sigma [N], dev out [N].  Asynchronous on the problem's stream. */
+ * over every node pair, in FP64 (YQ_FP64) or FP32 arithmetic (YQ_MIXED).  With
+ * the FMM enabled (far_mode) YQ_MIXED gives the FMM far field (step a7: FP64
+ * expansions, FP32 leaf-neighbour interactions) and YQ_FMM64 the FMM with FP64
+ * leaf-neighbour interactions.  dev sigma [N], dev out [N].  Asynchronous.
+ *
+ * With the FMM enabled, YQ_MIXED operator applications (yq_apply_operator and
+ * the inner GMRES of a YQ_MIXED solve) use the FMM far field; YQ_FP64 ones, and
+ * so every refinement residual, stay the exact direct sum. */
 int yq_apply_far(yq_problem* prob, const double* sigma, double* out, int32_t precision);
 
 /* The discrete operator (steps a5 + a6): out = (1/2 I + D) sigma with the

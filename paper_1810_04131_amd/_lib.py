@@ -17,6 +17,7 @@ YQ_ESTATE = -6
 YQ_EADMIT = -7
 YQ_FP64 = 0
 YQ_MIXED = 1
+YQ_FMM64 = 2
 YQ_FAR_DIRECT = 0
 YQ_FAR_FMM = 1
 YQ_FAR_AUTO = 2

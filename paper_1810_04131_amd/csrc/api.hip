@@ -14,6 +14,9 @@ using namespace yq;
 
 namespace {
 
+// YQ_FAR_AUTO switches the inner operator to the FMM from this many nodes on.
+constexpr int64_t kFmmAutoNodes = 60000;
+
 thread_local std::string g_last_error;
 
 // Brackets the launches issued in its scope with a pair of events when profiling is on.
@@ -70,8 +73,10 @@ void check_params(const yq_params& p) {
   YQ_REQUIRE(p.qbx_radius > 0.0 && p.qbx_radius < 1.0, YQ_EINVAL, "qbx_radius must be in (0, 1)");
   YQ_REQUIRE(p.near_beta >= 0.0 && p.pot_beta >= 0.0, YQ_EINVAL, "near_beta, pot_beta >= 0");
   YQ_REQUIRE(p.precision == YQ_FP64 || p.precision == YQ_MIXED, YQ_EINVAL, "bad precision");
-  YQ_REQUIRE(p.far_mode == YQ_FAR_DIRECT || p.far_mode == YQ_FAR_AUTO, YQ_EINVAL,
-             "far_mode: only YQ_FAR_DIRECT / YQ_FAR_AUTO are available in this build");
+  YQ_REQUIRE(p.far_mode == YQ_FAR_DIRECT || p.far_mode == YQ_FAR_FMM || p.far_mode == YQ_FAR_AUTO,
+             YQ_EINVAL, "bad far_mode");
+  YQ_REQUIRE(p.fmm_order >= 1 && p.fmm_order <= MAXP, YQ_EINVAL, "fmm_order out of range 1..30");
+  YQ_REQUIRE(p.fmm_leaf_max >= 1, YQ_EINVAL, "fmm_leaf_max must be >= 1");
   YQ_REQUIRE(p.tol > 0.0 && p.maxiter >= 1 && p.restart >= 1 && p.restart <= 200, YQ_EINVAL,
              "tol > 0, maxiter >= 1, 1 <= restart <= 200");
   YQ_REQUIRE(p.inner_tol > 0.0 && p.inner_tol < 1.0 && p.max_refine >= 1, YQ_EINVAL,
@@ -98,9 +103,24 @@ std::vector<double> interp_for(const Consts& c, int nsub) {
 
 // ---- operator ------------------------------------------------------------------------------
 
+// The far field of the FP32-class (inner) operator comes from the FMM when it is
+// enabled; the FP64 operator is always the exact direct sum.
+void far_fmm(yq_problem* pb, const double* sigma) {
+  Timed t(pb, 1);
+  pb->fmm->apply(sigma, pb->partial.p, true, pb->tab.p, pb->stream);
+}
+
 void apply_op(yq_problem* pb, const double* sigma, double* out, int prec) {
   GeomView g = pb->view();
   const int win = pb->prm.qbx_window;
+  if (prec == YQ_MIXED && pb->fmm) {
+    far_fmm(pb, sigma);
+    FarPlan one{pb->fp.tblocks, 1, (int)pb->N};
+    Timed t(pb, 2);
+    launch_finish(g, win, one, pb->partial.p, nullptr, pb->W.p, pb->xrow.p, pb->xpan.p,
+                  pb->xvals.p, sigma, out, pb->stream);
+    return;
+  }
   if (prec == YQ_MIXED) {
     {
       Timed t(pb, 1);
@@ -460,6 +480,14 @@ int yq_set_particles(yq_problem* pb, int32_t n, const double* center_xy, const d
     launch_to_f32(pb->wny.p, pb->wny32.p, N, s);
 
     pb->fp = far_plan(N, N, 256, pb->far_want);
+    pb->fmm.reset();
+    const bool use_fmm = pb->prm.far_mode == YQ_FAR_FMM ||
+                         (pb->prm.far_mode == YQ_FAR_AUTO && N >= kFmmAutoNodes);
+    if (use_fmm && !pb->batch_member) {
+      pb->fmm = std::make_unique<Fmm>();
+      pb->fmm->build(pb->x.p, pb->y.p, pb->wnx.p, pb->wny.p, N, kappa, pb->prm.fmm_order,
+                     pb->prm.fmm_leaf_max, pb->tab.p, s);
+    }
     pb->partial.alloc((size_t)pb->fp.chunks * N);
     pb->partial32.alloc((size_t)pb->fp.chunks * N);
     pb->f.alloc(N);
@@ -548,8 +576,17 @@ int yq_apply_far(yq_problem* pb, const double* sigma, double* out, int32_t preci
   return guarded(pb, [&] {
     require_ready(pb);
     YQ_REQUIRE(sigma && out, YQ_EINVAL, "null argument");
-    YQ_REQUIRE(precision == YQ_FP64 || precision == YQ_MIXED, YQ_EINVAL, "bad precision");
+    YQ_REQUIRE(precision == YQ_FP64 || precision == YQ_MIXED ||
+                   (precision == YQ_FMM64 && pb->fmm),
+               YQ_EINVAL, "bad precision");
     GeomView g = pb->view();
+    if ((precision == YQ_MIXED || precision == YQ_FMM64) && pb->fmm) {
+      pb->fmm->apply(sigma, pb->partial.p, precision == YQ_MIXED, pb->tab.p, pb->stream);
+      FarPlan one{pb->fp.tblocks, 1, (int)pb->N};
+      launch_finish(g, -1, one, pb->partial.p, nullptr, pb->W.p, pb->xrow.p, pb->xpan.p, nullptr,
+                    sigma, out, pb->stream);
+      return;
+    }
     // far field with a zero near correction: reuse finish with window 0 rows skipped
     if (precision == YQ_MIXED)
       launch_far32(pb->x.p, pb->y.p, pb->wnx32.p, pb->wny32.p, sigma, pb->N, pb->kappa,

@@ -1,0 +1,45 @@
+// Quadtree Yukawa FMM for the double-layer far field (fmm.hip).
+#pragma once
+
+#include <vector>
+
+#include "common.h"
+
+namespace yq {
+
+struct FmmLevel {
+  int nbox = 0;
+  double w = 0.0;                 // box width
+  std::vector<int64_t> key;       // Morton keys (sorted)
+  DevBuf<double> cx, cy;          // centres
+  DevBuf<int> parent;             // index at level - 1
+  DevBuf<int> cpos;               // position (0..3) in the parent
+  DevBuf<int> ch;                 // children indices at level + 1 [4 * nbox], -1 if empty
+  DevBuf<int> ilp, ils, ilo;      // interaction list: CSR over targets, source box, offset id
+  DevBuf<double2> M, L;           // expansions [nbox * (p + 1)]
+};
+
+struct Fmm {
+  int p = 20;
+  int depth = 0;
+  int leaf_max = 64;
+  double x0 = 0.0, y0 = 0.0, W = 1.0, kappa = 1.0;
+  int64_t N = 0;
+  std::vector<FmmLevel> lv;       // 0..depth
+  DevBuf<int> perm;               // sorted position -> node index
+  DevBuf<double> xs, ys, wnxs, wnys, qx, qy, outs;
+  DevBuf<int> leaf_start, leaf_cnt;   // per leaf box
+  DevBuf<int> nbp, nbi;               // P2P neighbour leaves (CSR, self included)
+  DevBuf<double2> tg;  // M2M / L2L tables: [level][cpos 0..3][k + 2p], k in -2p..2p
+  DevBuf<double2> ts;  // M2L tables: [level][offset 0..48][k + 2p]
+  int max_leaf = 0;
+  bool built = false;
+
+  void build(const double* dx, const double* dy, const double* dwnx, const double* dwny,
+             int64_t n, double kappa, int order, int leaf_max, const double* tab, hipStream_t s);
+  // partial[i] = (2 pi / kappa^2) * far field at node i (the far-field kernels' scaling)
+  void apply(const double* sigma, double* partial, bool p2p_fp32, const double* tab,
+             hipStream_t s);
+};
+
+}  // namespace yq

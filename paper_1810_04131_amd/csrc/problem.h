@@ -5,6 +5,8 @@
 #include <vector>
 
 #include "common.h"
+#include "fmm.h"
+#include <memory>
 
 using namespace yq;
 
@@ -19,6 +21,7 @@ struct yq_problem {
   bool ready = false;
   bool have_f = false;
   bool batch_member = false;  // workspace for GMRES/forces comes from the batch
+  std::unique_ptr<Fmm> fmm;   // far-field FMM (inner operator) when enabled
   int far_want = 4096;        // far-field plan parameter (far_plan)
 
   std::vector<double> h_pc;  // [n*5]

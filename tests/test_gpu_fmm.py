@@ -1,0 +1,98 @@
+"""Quadtree Yukawa FMM (inner far field) against the direct sum and the oracle."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from oracle.geometry import Params
+
+pytestmark = pytest.mark.gpu
+
+yq = pytest.importorskip("paper_1810_04131_amd")
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _rel(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+@pytest.fixture(scope="module")
+def medium():
+    return workloads.config_medium(kappa=0.5, seed=1)
+
+
+def test_fmm_converges_to_direct_far_field(medium):
+    _torch()
+    parts = medium["particles"]
+    sig = workloads.random_density(25600, 3)
+    errs = {}
+    for p in (8, 14, 20, 26):
+        pb = yq.Problem(yq.default_params(far_mode=yq.YQ_FAR_FMM, fmm_order=p, fmm_leaf_max=64))
+        pb.set_workload(parts)
+        direct = _np(pb.apply_far(sig, yq.YQ_FP64))
+        errs[p] = _rel(_np(pb.apply_far(sig, yq.YQ_FMM64)), direct)
+        e32 = _rel(_np(pb.apply_far(sig, yq.YQ_MIXED)), direct)
+        assert e32 < max(errs[p], 0) + 5e-6
+    # geometric convergence in the expansion order (error bound ~ 0.55^p per translation)
+    assert errs[8] > errs[14] > errs[20] > errs[26]
+    assert errs[20] < 1e-5 and errs[26] < 1e-6, errs
+
+
+def test_fmm_far_field_against_oracle_rows(medium):
+    _torch()
+    parts = medium["particles"]
+    d = oracle.discretize(parts, Params(panels=32, qbx_order=10))
+    sig = workloads.random_density(d.N, 4)
+    pb = yq.Problem(yq.default_params(far_mode=yq.YQ_FAR_FMM, fmm_order=26))
+    pb.set_workload(parts)
+    rows = sorted(set(np.random.default_rng(5).integers(0, d.N, 16).tolist()))
+    ref = oracle.far_rows(d, rows, sig)
+    got = _np(pb.apply_far(sig, yq.YQ_FMM64))[rows]
+    assert np.abs(got - ref).max() < 1e-6 * np.abs(ref).max()
+
+
+def test_fmm_inner_solve_reaches_direct_tolerance():
+    _torch()
+    parts = workloads.random_ellipses(6, 12.0, 1.1, seed=7)
+    P, p = 16, 8
+    d = oracle.discretize(parts, Params(panels=P, qbx_order=p))
+    A = oracle.build_matrices(d)
+    f = oracle.arc_label(d)
+    so = oracle.lu_solve(A, f)
+    pb = yq.Problem(yq.default_params(panels_per_particle=P, qbx_order=p, far_mode=yq.YQ_FAR_FMM,
+                                      fmm_order=16, fmm_leaf_max=32, precision=yq.YQ_MIXED,
+                                      tol=1e-10))
+    pb.set_workload(parts)
+    pb.set_boundary_data(f)
+    sig, info = pb.solve()
+    # refinement residuals use the exact FP64 operator: the FMM only steers the inner solve
+    assert info["residual"] <= 1e-10 and info["matvecs_fp32"] > 0
+    assert _rel(_np(sig), so) < 1e-8
+
+
+def test_fmm_large_workload_residual_property():
+    _torch()
+    cfg = workloads.config_large(seed=0)
+    parts = cfg["particles"]
+    pb = yq.Problem(yq.default_params(far_mode=yq.YQ_FAR_FMM, fmm_order=20, fmm_leaf_max=64,
+                                      precision=yq.YQ_MIXED, tol=1e-8, maxiter=400))
+    pb.set_workload(parts)
+    assert pb.N == 256000
+    f = pb.boundary_label()
+    pb.set_boundary_data(f)
+    sig, info = pb.solve()
+    assert info["residual"] <= 1e-8
+    d = oracle.discretize(parts, Params(panels=32, qbx_order=10))
+    rows = sorted(set(np.random.default_rng(2).integers(0, d.N, 8).tolist()))
+    r = oracle.apply_rows(d, rows, _np(sig)) - oracle.arc_label(d)[rows]
+    assert np.abs(r).max() < 1e-6
