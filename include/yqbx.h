@@ -78,6 +78,9 @@ typedef struct yq_params {
   int32_t restart;             /* GMRES: Krylov dimension before a restart (<= 200) */
   double inner_tol;            /* YQ_MIXED: relative tolerance of each FP32-operator inner solve */
   int32_t max_refine;          /* YQ_MIXED: maximum refinement (outer) steps */
+  int32_t fmm_resid_order;     /* FMM enabled: order of the FP64 FMM used for refinement residuals,
+                                  FP64 solves and the reported residual (relative operator error
+                                  ~1e-10 at 40); 0 = the exact direct sum */
 } yq_params;
 
 typedef struct yq_solve_info {
@@ -92,7 +95,7 @@ typedef struct yq_solve_info {
 /* Defaults: P = 32, p = 10, window 2, oversample 4, radius 0.25, near_beta 0.5,
  * near_oversample 4, pot_oversample 8, pot_beta 0.5, FP64, direct far field,
  * FMM order 20 / 64 per leaf, tol 1e-10, maxiter 200, restart 100,
- * inner_tol 1e-6, max_refine 8. */
+ * inner_tol 1e-6, max_refine 8, fmm_resid_order 40. */
 void yq_default_params(yq_params* params);
 
 /* Creates a problem on the current HIP device.  params: host, copied. */
@@ -146,8 +149,10 @@ int yq_set_boundary_data(yq_problem* prob, const double* f);
  * leaf-neighbour interactions.  dev sigma [N], dev out [N].  Asynchronous.
  *
  * With the FMM enabled, YQ_MIXED operator applications (yq_apply_operator and
- * the inner GMRES of a YQ_MIXED solve) use the FMM far field; YQ_FP64 ones, and
- * so every refinement residual, stay the exact direct sum. */
+ * the inner GMRES of a YQ_MIXED solve) use the FMM far field; refinement
+ * residuals, FP64 solves and the reported residual use the order
+ * fmm_resid_order FMM with FP64 near interactions (or the exact direct sum when
+ * it is 0); yq_apply_operator(YQ_FP64) is always the exact direct sum. */
 int yq_apply_far(yq_problem* prob, const double* sigma, double* out, int32_t precision);
 
 /* The discrete operator (steps a5 + a6): out = (1/2 I + D) sigma with the

@@ -51,6 +51,7 @@ class yq_params(ctypes.Structure):
         ("restart", c_int32),
         ("inner_tol", c_double),
         ("max_refine", c_int32),
+        ("fmm_resid_order", c_int32),
     ]
 
 

@@ -75,7 +75,9 @@ void check_params(const yq_params& p) {
   YQ_REQUIRE(p.precision == YQ_FP64 || p.precision == YQ_MIXED, YQ_EINVAL, "bad precision");
   YQ_REQUIRE(p.far_mode == YQ_FAR_DIRECT || p.far_mode == YQ_FAR_FMM || p.far_mode == YQ_FAR_AUTO,
              YQ_EINVAL, "bad far_mode");
-  YQ_REQUIRE(p.fmm_order >= 1 && p.fmm_order <= MAXP, YQ_EINVAL, "fmm_order out of range 1..30");
+  YQ_REQUIRE(p.fmm_order >= 1 && p.fmm_order <= MAXP_FMM, YQ_EINVAL, "fmm_order out of range 1..48");
+  YQ_REQUIRE(p.fmm_resid_order >= 0 && p.fmm_resid_order <= MAXP_FMM, YQ_EINVAL,
+             "fmm_resid_order out of range 0..48");
   YQ_REQUIRE(p.fmm_leaf_max >= 1, YQ_EINVAL, "fmm_leaf_max must be >= 1");
   YQ_REQUIRE(p.tol > 0.0 && p.maxiter >= 1 && p.restart >= 1 && p.restart <= 200, YQ_EINVAL,
              "tol > 0, maxiter >= 1, 1 <= restart <= 200");
@@ -141,6 +143,31 @@ void apply_op(yq_problem* pb, const double* sigma, double* out, int prec) {
   }
 }
 
+// The operator of refinement residuals, FP64 solves and reported residuals: the
+// higher-order FP64 FMM when it is enabled, otherwise the exact direct sum.
+constexpr int OP_RESID = 2;
+void apply_resid(yq_problem* pb, const double* sigma, double* out) {
+  if (!pb->fmm_hi) {
+    apply_op(pb, sigma, out, YQ_FP64);
+    return;
+  }
+  {
+    Timed t(pb, 0);
+    pb->fmm_hi->apply(sigma, pb->partial.p, false, pb->tab.p, pb->stream);
+  }
+  FarPlan one{pb->fp.tblocks, 1, (int)pb->N};
+  Timed t(pb, 2);
+  launch_finish(pb->view(), pb->prm.qbx_window, one, pb->partial.p, nullptr, pb->W.p, pb->xrow.p,
+                pb->xpan.p, pb->xvals.p, sigma, out, pb->stream);
+}
+
+void apply_any(yq_problem* pb, const double* sigma, double* out, int prec) {
+  if (prec == OP_RESID)
+    apply_resid(pb, sigma, out);
+  else
+    apply_op(pb, sigma, out, prec);
+}
+
 // ---- GMRES -----------------------------------------------------------------------------------
 
 double dot_host(yq_problem* pb, const double* a, const double* b) {
@@ -189,7 +216,7 @@ GmresResult gmres(yq_problem* pb, int prec, const double* b, double* x, bool x_z
     if (first && x_zero) {
       YQ_HIP(hipMemcpyAsync(r, b, N * sizeof(double), hipMemcpyDeviceToDevice, s));
     } else {
-      apply_op(pb, x, w, prec);
+      apply_any(pb, x, w, prec);
       ++R.matvecs;
       launch_axpby(-1.0, w, 1.0, b, r, N, s);
     }
@@ -210,7 +237,7 @@ GmresResult gmres(yq_problem* pb, int prec, const double* b, double* x, bool x_z
     for (; j < m && R.iterations < maxit; ++j) {
       double* vj = V + (int64_t)j * N;
       double* vn = V + (int64_t)(j + 1) * N;
-      apply_op(pb, vj, w, prec);
+      apply_any(pb, vj, w, prec);
       ++R.matvecs;
       // classical Gram-Schmidt, twice
       launch_multidot(V, N, j + 1, w, N, pb->kpart.p, nb, s);
@@ -311,6 +338,7 @@ void yq_default_params(yq_params* p) {
   p->restart = 100;
   p->inner_tol = 1e-6;
   p->max_refine = 8;
+  p->fmm_resid_order = 40;
 }
 
 const char* yq_error_string(int status) {
@@ -481,12 +509,18 @@ int yq_set_particles(yq_problem* pb, int32_t n, const double* center_xy, const d
 
     pb->fp = far_plan(N, N, 256, pb->far_want);
     pb->fmm.reset();
+    pb->fmm_hi.reset();
     const bool use_fmm = pb->prm.far_mode == YQ_FAR_FMM ||
                          (pb->prm.far_mode == YQ_FAR_AUTO && N >= kFmmAutoNodes);
     if (use_fmm && !pb->batch_member) {
       pb->fmm = std::make_unique<Fmm>();
       pb->fmm->build(pb->x.p, pb->y.p, pb->wnx.p, pb->wny.p, N, kappa, pb->prm.fmm_order,
                      pb->prm.fmm_leaf_max, pb->tab.p, s);
+      if (pb->prm.fmm_resid_order > 0) {
+        pb->fmm_hi = std::make_unique<Fmm>();
+        pb->fmm_hi->build(pb->x.p, pb->y.p, pb->wnx.p, pb->wny.p, N, kappa,
+                          pb->prm.fmm_resid_order, pb->prm.fmm_leaf_max, pb->tab.p, s);
+      }
     }
     pb->partial.alloc((size_t)pb->fp.chunks * N);
     pb->partial32.alloc((size_t)pb->fp.chunks * N);
@@ -624,7 +658,7 @@ int yq_solve(yq_problem* pb, const double* sigma0, double* sigma, yq_solve_info*
     bool conv = false;
     double* r = pb->kd.p;  // refinement residual
     if (pb->prm.precision == YQ_FP64) {
-      GmresResult R = gmres(pb, YQ_FP64, pb->f.p, sigma, zero, pb->prm.tol, pb->prm.maxiter);
+      GmresResult R = gmres(pb, OP_RESID, pb->f.p, sigma, zero, pb->prm.tol, pb->prm.maxiter);
       inf.iterations = R.iterations;
       inf.outer_steps = R.cycles;
       inf.matvecs_fp64 = R.matvecs;
@@ -642,7 +676,7 @@ int yq_solve(yq_problem* pb, const double* sigma0, double* sigma, yq_solve_info*
           YQ_HIP(hipMemcpyAsync(r, pb->f.p, N * sizeof(double), hipMemcpyDeviceToDevice, s));
           rel = 1.0;
         } else {
-          apply_op(pb, sigma, pb->kw.p, YQ_FP64);
+          apply_resid(pb, sigma, pb->kw.p);
           ++inf.matvecs_fp64;
           launch_axpby(-1.0, pb->kw.p, 1.0, pb->f.p, r, N, s);
           rel = fnorm > 0.0 ? std::sqrt(dot_host(pb, r, r)) / fnorm : 0.0;
@@ -661,8 +695,8 @@ int yq_solve(yq_problem* pb, const double* sigma0, double* sigma, yq_solve_info*
         launch_axpby(1.0, delta.p, 1.0, sigma, sigma, N, s);
       }
     }
-    // true FP64 residual
-    apply_op(pb, sigma, pb->kw.p, YQ_FP64);
+    // final FP64 residual
+    apply_resid(pb, sigma, pb->kw.p);
     ++inf.matvecs_fp64;
     launch_axpby(-1.0, pb->kw.p, 1.0, pb->f.p, r, N, s);
     const double fn = std::sqrt(dot_host(pb, pb->f.p, pb->f.p));

@@ -13,6 +13,7 @@ namespace yq {
 
 constexpr int Q = 16;            // Gauss-Legendre nodes per panel
 constexpr int MAXP = 30;         // largest QBX order
+constexpr int MAXP_FMM = 48;     // largest FMM order
 constexpr int MAXSUB = 16;       // largest oversampling factor
 constexpr double PI = 3.14159265358979323846264338327950288;
 constexpr int T_SIZE_HOST = 104;  // doubles in the FP64 coefficient table (bessel.h T_SIZE)

@@ -74,7 +74,7 @@ __global__ void tab_g_kernel(int depth, int p, double W, double kappa, double2* 
   const double w = W / (double)(1 << l);
   const double dx = (pos & 1 ? 0.5 : -0.5) * w, dy = (pos & 2 ? 0.5 : -0.5) * w;
   const double r = sqrt(dx * dx + dy * dy), ph = atan2(dy, dx);
-  double I[2 * MAXP + 1];
+  double I[2 * MAXP_FMM + 1];
   iseries(kappa * r, 2 * p, I, 1);
   for (int k = -2 * p; k <= 2 * p; ++k) {
     double s, c;
@@ -102,7 +102,7 @@ __global__ void tab_s_kernel(int depth, int p, double W, double kappa, const dou
   const double dx = -ox * w, dy = -oy * w;
   const double r = sqrt(dx * dx + dy * dy), ph = atan2(dy, dx);
   const double z = kappa * r;
-  double Kn[2 * MAXP + 1];
+  double Kn[2 * MAXP_FMM + 1];
   double k0, k1;
   k01_64(z, k0, k1, tab);
   Kn[0] = k0;
@@ -130,7 +130,8 @@ __global__ void gather_kernel(int64_t N, const int* __restrict__ perm, const dou
 
 constexpr int FB = 64;
 
-// One block per leaf: multipole coefficients M_n, n = 0..p.
+// One block per leaf (blockDim.x threads, LDS scaled to it): multipole
+// coefficients M_n, n = 0..p.
 __global__ __launch_bounds__(FB) void p2m_kernel(int p, double kappa, const int* __restrict__ ls,
                                                  const int* __restrict__ lc,
                                                  const double* __restrict__ ccx,
@@ -142,19 +143,20 @@ __global__ __launch_bounds__(FB) void p2m_kernel(int p, double kappa, const int*
                                                  double2* __restrict__ M) {
   extern __shared__ double sh[];
   const int tid = threadIdx.x;
+  const int B = blockDim.x;
   const int b = blockIdx.x;
-  double* I = sh;                      // [(p + 2) * FB]
-  double* acc = sh + (p + 2) * FB;     // [2 (p + 1) * FB]
+  double* I = sh;                      // [(p + 2) * B]
+  double* acc = sh + (p + 2) * B;      // [2 (p + 1) * B]
   for (int n = 0; n <= p; ++n) {
-    acc[(2 * n) * FB + tid] = 0.0;
-    acc[(2 * n + 1) * FB + tid] = 0.0;
+    acc[(2 * n) * B + tid] = 0.0;
+    acc[(2 * n + 1) * B + tid] = 0.0;
   }
   const int s0 = ls[b], cnt = lc[b];
   const double cx = ccx[b], cy = ccy[b];
-  for (int j = tid; j < cnt; j += FB) {
+  for (int j = tid; j < cnt; j += B) {
     const double dx = xs[s0 + j] - cx, dy = ys[s0 + j] - cy;
     const double rho = sqrt(dx * dx + dy * dy);
-    iseries(kappa * rho, p + 1, I + tid, FB);
+    iseries(kappa * rho, p + 1, I + tid, B);
     const double2 e1 = rho > 0.0 ? make_double2(dx / rho, dy / rho) : make_double2(1.0, 0.0);
     const double2 Q = make_double2(qx[s0 + j], qy[s0 + j]);
     const double2 Qc = cconj(Q);
@@ -162,28 +164,28 @@ __global__ __launch_bounds__(FB) void p2m_kernel(int p, double kappa, const int*
     for (int n = 0; n <= p; ++n) {
       double2 gm;
       if (n == 0) {
-        const double i1 = I[1 * FB + tid];
+        const double i1 = I[1 * B + tid];
         gm = make_double2(i1 * e1.x, i1 * e1.y);                    // g_1
       } else {
-        const double im = I[(n - 1) * FB + tid];
+        const double im = I[(n - 1) * B + tid];
         gm = make_double2(im * Em.x, -im * Em.y);                  // conj(g_{n-1})
       }
-      const double ip = I[(n + 1) * FB + tid];
+      const double ip = I[(n + 1) * B + tid];
       const double2 gp = make_double2(ip * Ep.x, -ip * Ep.y);     // conj(g_{n+1})
-      double2 a = make_double2(acc[(2 * n) * FB + tid], acc[(2 * n + 1) * FB + tid]);
+      double2 a = make_double2(acc[(2 * n) * B + tid], acc[(2 * n + 1) * B + tid]);
       a = cmad(Qc, gm, a);
       a = cmad(Q, gp, a);
-      acc[(2 * n) * FB + tid] = a.x;
-      acc[(2 * n + 1) * FB + tid] = a.y;
+      acc[(2 * n) * B + tid] = a.x;
+      acc[(2 * n + 1) * B + tid] = a.y;
       Em = (n == 0) ? make_double2(1.0, 0.0) : cmul(Em, e1);
       Ep = cmul(Ep, e1);
     }
   }
   __syncthreads();
   const double sc = kappa / (4.0 * PI);
-  for (int v = tid; v < 2 * (p + 1); v += FB) {
+  for (int v = tid; v < 2 * (p + 1); v += B) {
     double s = 0.0;
-    for (int t = 0; t < FB; ++t) s += acc[v * FB + t];
+    for (int t = 0; t < B; ++t) s += acc[v * B + t];
     const int n = v >> 1;
     if (v & 1)
       M[(int64_t)b * (p + 1) + n].y = s * sc;
@@ -357,7 +359,7 @@ static void up(DevBuf<T>& d, const std::vector<T>& h, hipStream_t s) {
 
 void Fmm::build(const double* dx, const double* dy, const double* dwnx, const double* dwny, int64_t n,
                 double kap, int order, int lmax, const double* tab, hipStream_t s) {
-  YQ_REQUIRE(order >= 1 && order <= MAXP, YQ_EINVAL, "fmm_order must be in 1..30");
+  YQ_REQUIRE(order >= 1 && order <= MAXP_FMM, YQ_EINVAL, "FMM order must be in 1..48");
   YQ_REQUIRE(lmax >= 1, YQ_EINVAL, "fmm_leaf_max must be >= 1");
   p = order;
   leaf_max = lmax;
@@ -536,8 +538,9 @@ void Fmm::apply(const double* sigma, double* partial, bool p2p_fp32, const doubl
   gather_kernel<<<(unsigned)((N + 255) / 256), 256, 0, s>>>(N, perm.p, sigma, wnxs.p, wnys.p, qx.p,
                                                             qy.p);
   FmmLevel& leaf = lv[depth];
-  const size_t sh_p2m = (size_t)(3 * p + 4) * FB * sizeof(double);
-  p2m_kernel<<<leaf.nbox, FB, sh_p2m, s>>>(p, kappa, leaf_start.p, leaf_cnt.p, leaf.cx.p, leaf.cy.p,
+  const int pb = (3 * p + 4) * FB * sizeof(double) <= 48 * 1024 ? FB : FB / 2;
+  const size_t sh_p2m = (size_t)(3 * p + 4) * pb * sizeof(double);
+  p2m_kernel<<<leaf.nbox, pb, sh_p2m, s>>>(p, kappa, leaf_start.p, leaf_cnt.p, leaf.cx.p, leaf.cy.p,
                                            xs.p, ys.p, qx.p, qy.p, leaf.M.p);
   for (int l = depth - 1; l >= 2; --l) {
     const int64_t nt = (int64_t)lv[l].nbox * (p + 1);

@@ -21,7 +21,8 @@ struct yq_problem {
   bool ready = false;
   bool have_f = false;
   bool batch_member = false;  // workspace for GMRES/forces comes from the batch
-  std::unique_ptr<Fmm> fmm;   // far-field FMM (inner operator) when enabled
+  std::unique_ptr<Fmm> fmm;     // far-field FMM (inner operator) when enabled
+  std::unique_ptr<Fmm> fmm_hi;  // higher-order FP64 FMM for residuals (fmm_resid_order > 0)
   int far_want = 4096;        // far-field plan parameter (far_plan)
 
   std::vector<double> h_pc;  // [n*5]

@@ -61,7 +61,8 @@ def test_fmm_far_field_against_oracle_rows(medium):
     assert np.abs(got - ref).max() < 1e-6 * np.abs(ref).max()
 
 
-def test_fmm_inner_solve_reaches_direct_tolerance():
+@pytest.mark.parametrize("resid_order", [0, 40])
+def test_fmm_inner_solve_reaches_direct_tolerance(resid_order):
     _torch()
     parts = workloads.random_ellipses(6, 12.0, 1.1, seed=7)
     P, p = 16, 8
@@ -71,12 +72,16 @@ def test_fmm_inner_solve_reaches_direct_tolerance():
     so = oracle.lu_solve(A, f)
     pb = yq.Problem(yq.default_params(panels_per_particle=P, qbx_order=p, far_mode=yq.YQ_FAR_FMM,
                                       fmm_order=16, fmm_leaf_max=32, precision=yq.YQ_MIXED,
-                                      tol=1e-10))
+                                      tol=1e-10, fmm_resid_order=resid_order))
     pb.set_workload(parts)
     pb.set_boundary_data(f)
     sig, info = pb.solve()
-    # refinement residuals use the exact FP64 operator: the FMM only steers the inner solve
+    # the FMM only steers the inner solve; refinement residuals use the exact
+    # operator (order 0) or the order-40 FP64 FMM, whose operator error is far
+    # below the tolerance, so the exact residual also meets it
     assert info["residual"] <= 1e-10 and info["matvecs_fp32"] > 0
+    exact = _np(pb.apply_operator(sig, yq.YQ_FP64)) - f
+    assert np.linalg.norm(exact) <= 2e-10 * np.linalg.norm(f)
     assert _rel(_np(sig), so) < 1e-8
 
 
@@ -92,6 +97,8 @@ def test_fmm_large_workload_residual_property():
     pb.set_boundary_data(f)
     sig, info = pb.solve()
     assert info["residual"] <= 1e-8
+    exact = pb.apply_operator(sig, yq.YQ_FP64) - f
+    assert (exact.norm() / f.norm()).item() <= 2e-8
     d = oracle.discretize(parts, Params(panels=32, qbx_order=10))
     rows = sorted(set(np.random.default_rng(2).integers(0, d.N, 8).tolist()))
     r = oracle.apply_rows(d, rows, _np(sig)) - oracle.arc_label(d)[rows]
