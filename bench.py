@@ -57,7 +57,7 @@ def parse():
     ap.add_argument("--fp64-steps", type=int, default=3)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy (counter calibration)")
-    ap.add_argument("--workload", choices=["medium", "batch", "serve"], default="medium",
+    ap.add_argument("--workload", choices=["medium", "batch", "serve", "large"], default="medium",
                     help="medium: the 50-ellipse solve (default line); batch: many configurations "
                          "per fused launch; serve: Poisson-arrival continuous batching")
     ap.add_argument("--configs", type=int, default=128, help="batch: number of configurations")
@@ -306,6 +306,57 @@ def bench_serve(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_large(args):
+    """500 ellipses (N = 256,000) with the FMM inner far field and FP64 FMM residuals."""
+    import numpy as np
+    import torch
+
+    import paper_1810_04131_amd as yq
+    import workloads
+    cfg = workloads.config_large(seed=0)
+    parts = cfg["particles"]
+    prm = yq.default_params(far_mode=yq.YQ_FAR_FMM, fmm_order=20, fmm_leaf_max=64,
+                            fmm_resid_order=40, precision=yq.YQ_MIXED, tol=1e-8, maxiter=400)
+    pb = yq.Problem(prm)
+    for _ in range(max(args.warmup, 1)):
+        pb.set_workload(parts)
+        pb.set_boundary_data(pb.boundary_label())
+        pb.solve()
+    pb.lib.yq_profile_enable(pb.h, 1)
+    for ph in range(6):
+        prof(pb, ph)
+    lat, lat_setup = [], []
+    for _ in range(max(args.steps, 1)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pb.set_workload(parts)
+        pb.set_boundary_data(pb.boundary_label())
+        t1 = time.perf_counter()
+        sig, info = pb.solve()
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - t0)
+        lat_setup.append(t1 - t0)
+    n32, ms32 = prof(pb, 1)
+    n64, ms64 = prof(pb, 0)
+    N = pb.N
+    out = {
+        "metric": "source-target interactions/s per matvec; solves/s + p50/p99 latency at 1e-8 rel err",
+        "value": float(N) * N / (ms32 / max(n32, 1) * 1e-3), "unit": "interactions/s (FMM, dense-equivalent)",
+        "n_gpus": 1, "steps": len(lat), "warmup": args.warmup,
+        "ms_per_step": percentile(lat, 0.5) * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": "500 ellipses A~U[0.8,1.2] B~U[0.4,0.6] in 100x100, N=256000, kappa=1, "
+                               "QBX order 10, FMM order 20 (<=64 nodes/leaf) inner, FP64 FMM order 40 "
+                               "residuals, tol 1e-8", "N": N, "parallelism": "single GPU"},
+        "solves_per_s": 1.0 / percentile(lat, 0.5), "latency_ms_p50": percentile(lat, 0.5) * 1e3,
+        "latency_ms_p99": percentile(lat, 0.99) * 1e3, "setup_ms_p50": percentile(lat_setup, 0.5) * 1e3,
+        "gmres_iterations": info["iterations"], "refine_steps": info["outer_steps"],
+        "residual": info["residual"], "fmm_inner_ms": ms32 / max(n32, 1),
+        "fmm_resid_ms": ms64 / max(n64, 1),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.copy_probe:
@@ -315,6 +366,8 @@ def main():
         return bench_batch(args)
     if args.workload == "serve":
         return bench_serve(args)
+    if args.workload == "large":
+        return bench_large(args)
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}))

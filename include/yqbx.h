@@ -56,6 +56,7 @@ enum { YQ_FP64 = 0, YQ_MIXED = 1 };                       /* precision */
 enum { YQ_FMM64 = 2 };  /* yq_apply_far only: FMM expansions with FP64 near interactions */
 enum { YQ_FAR_DIRECT = 0, YQ_FAR_FMM = 1, YQ_FAR_AUTO = 2 };   /* far-field mode */
 enum { YQ_LABEL_ARC = 0, YQ_LABEL_JANUS = 1 };             /* boundary labels */
+enum { YQ_M2L_MFMA = 0, YQ_M2L_VALU = 1 };                 /* FMM M2L kernel */
 
 typedef struct yq_problem yq_problem;
 
@@ -81,6 +82,8 @@ typedef struct yq_params {
   int32_t fmm_resid_order;     /* FMM enabled: order of the FP64 FMM used for refinement residuals,
                                   FP64 solves and the reported residual (relative operator error
                                   ~1e-10 at 40); 0 = the exact direct sum */
+  int32_t fmm_m2l;             /* FMM M2L translations: YQ_M2L_MFMA (FP64 matrix-core products)
+                                  or YQ_M2L_VALU (one lane per coefficient); same results to rounding */
 } yq_params;
 
 typedef struct yq_solve_info {
@@ -95,7 +98,7 @@ typedef struct yq_solve_info {
 /* Defaults: P = 32, p = 10, window 2, oversample 4, radius 0.25, near_beta 0.5,
  * near_oversample 4, pot_oversample 8, pot_beta 0.5, FP64, direct far field,
  * FMM order 20 / 64 per leaf, tol 1e-10, maxiter 200, restart 100,
- * inner_tol 1e-6, max_refine 8, fmm_resid_order 40. */
+ * inner_tol 1e-6, max_refine 8, fmm_resid_order 40, fmm_m2l YQ_M2L_MFMA. */
 void yq_default_params(yq_params* params);
 
 /* Creates a problem on the current HIP device.  params: host, copied. */

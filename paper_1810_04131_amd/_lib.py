@@ -23,6 +23,8 @@ YQ_FAR_FMM = 1
 YQ_FAR_AUTO = 2
 YQ_LABEL_ARC = 0
 YQ_LABEL_JANUS = 1
+YQ_M2L_MFMA = 0
+YQ_M2L_VALU = 1
 
 c_int32 = ctypes.c_int32
 c_int64 = ctypes.c_int64
@@ -52,6 +54,7 @@ class yq_params(ctypes.Structure):
         ("inner_tol", c_double),
         ("max_refine", c_int32),
         ("fmm_resid_order", c_int32),
+        ("fmm_m2l", c_int32),
     ]
 
 
@@ -136,6 +139,11 @@ def load():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with paper_1810_04131_amd/build.py")
+    # The library must run on PyTorch's HIP runtime, whose tensors and streams it
+    # is handed: with torch's runtime mapped first, the library's dependency on
+    # libamdhip64 resolves to it.  Opened first, it would pull in a second HIP
+    # and HSA runtime next to torch's, and device allocations fail.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     for name, (res, args) in SIGNATURES.items():
         fn = getattr(lib, name)

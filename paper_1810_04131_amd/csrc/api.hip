@@ -79,6 +79,7 @@ void check_params(const yq_params& p) {
   YQ_REQUIRE(p.fmm_resid_order >= 0 && p.fmm_resid_order <= MAXP_FMM, YQ_EINVAL,
              "fmm_resid_order out of range 0..48");
   YQ_REQUIRE(p.fmm_leaf_max >= 1, YQ_EINVAL, "fmm_leaf_max must be >= 1");
+  YQ_REQUIRE(p.fmm_m2l == YQ_M2L_MFMA || p.fmm_m2l == YQ_M2L_VALU, YQ_EINVAL, "bad fmm_m2l");
   YQ_REQUIRE(p.tol > 0.0 && p.maxiter >= 1 && p.restart >= 1 && p.restart <= 200, YQ_EINVAL,
              "tol > 0, maxiter >= 1, 1 <= restart <= 200");
   YQ_REQUIRE(p.inner_tol > 0.0 && p.inner_tol < 1.0 && p.max_refine >= 1, YQ_EINVAL,
@@ -339,6 +340,7 @@ void yq_default_params(yq_params* p) {
   p->inner_tol = 1e-6;
   p->max_refine = 8;
   p->fmm_resid_order = 40;
+  p->fmm_m2l = YQ_M2L_MFMA;
 }
 
 const char* yq_error_string(int status) {
@@ -514,12 +516,13 @@ int yq_set_particles(yq_problem* pb, int32_t n, const double* center_xy, const d
                          (pb->prm.far_mode == YQ_FAR_AUTO && N >= kFmmAutoNodes);
     if (use_fmm && !pb->batch_member) {
       pb->fmm = std::make_unique<Fmm>();
+      pb->fmm->use_mfma = pb->prm.fmm_m2l == YQ_M2L_MFMA;
       pb->fmm->build(pb->x.p, pb->y.p, pb->wnx.p, pb->wny.p, N, kappa, pb->prm.fmm_order,
                      pb->prm.fmm_leaf_max, pb->tab.p, s);
       if (pb->prm.fmm_resid_order > 0) {
         pb->fmm_hi = std::make_unique<Fmm>();
-        pb->fmm_hi->build(pb->x.p, pb->y.p, pb->wnx.p, pb->wny.p, N, kappa,
-                          pb->prm.fmm_resid_order, pb->prm.fmm_leaf_max, pb->tab.p, s);
+        pb->fmm_hi->use_mfma = pb->prm.fmm_m2l == YQ_M2L_MFMA;
+        pb->fmm_hi->copy_tree(*pb->fmm, pb->prm.fmm_resid_order, pb->tab.p, s);
       }
     }
     pb->partial.alloc((size_t)pb->fp.chunks * N);

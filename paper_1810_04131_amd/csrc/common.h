@@ -70,7 +70,8 @@ struct DevBuf {
     hipError_t e = hipMalloc(&p, count * sizeof(T));
     if (e != hipSuccess) {
       p = nullptr;
-      throw Error{YQ_ENOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed"};
+      throw Error{YQ_ENOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) +
+                                 " bytes failed: " + hipGetErrorString(e)};
     }
     n = count;
   }

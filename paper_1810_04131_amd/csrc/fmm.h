@@ -16,6 +16,7 @@ struct FmmLevel {
   DevBuf<int> cpos;               // position (0..3) in the parent
   DevBuf<int> ch;                 // children indices at level + 1 [4 * nbox], -1 if empty
   DevBuf<int> ilp, ils, ilo;      // interaction list: CSR over targets, source box, offset id
+  DevBuf<int> ild;                // the same as a dense table [nbox * 49] (-1: none)
   DevBuf<double2> M, L;           // expansions [nbox * (p + 1)]
 };
 
@@ -34,9 +35,14 @@ struct Fmm {
   DevBuf<double2> ts;  // M2L tables: [level][offset 0..48][k + 2p]
   int max_leaf = 0;
   bool built = false;
+  bool use_mfma = true;   // M2L on the matrix cores (FP64 MFMA)
+  int R16 = 0;            // 2 (p + 1) rounded up to a multiple of 16
+  DevBuf<double> amat;    // M2L matrices [level][offset][R16][R16]
 
   void build(const double* dx, const double* dy, const double* dwnx, const double* dwny,
              int64_t n, double kappa, int order, int leaf_max, const double* tab, hipStream_t s);
+  void set_order(int q, const double* tab, hipStream_t s);
+  void copy_tree(const Fmm& o, int q, const double* tab, hipStream_t s);
   // partial[i] = (2 pi / kappa^2) * far field at node i (the far-field kernels' scaling)
   void apply(const double* sigma, double* partial, bool p2p_fp32, const double* tab,
              hipStream_t s);

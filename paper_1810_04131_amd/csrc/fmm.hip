@@ -25,6 +25,7 @@
 #include <algorithm>
 #include <cmath>
 #include <numeric>
+#include <type_traits>
 #include <unordered_map>
 
 #include "bessel.h"
@@ -236,6 +237,93 @@ __global__ void m2l_kernel(int p, int nbox, const int* __restrict__ ilp, const i
   L[t] = sum;
 }
 
+// ---- M2L as batched dense products on the matrix cores --------------------------------------
+//
+// With x = (Re M_0..Re M_p, Im M_0..Im M_p) and y likewise for L, one M2L term
+// is y += A_o x, A_o a real 2(p+1) x 2(p+1) matrix per (level, offset) that
+// carries (-1)^m and the M_{-n} = conj(M_n) fold.  A wave computes 16 target
+// boxes at once: for every offset, B = the 16 gathered source vectors (zero
+// where a target has no source at that offset), D += A_o B with
+// v_mfma_f64_16x16x4f64 tiles (FP64, so the FMM keeps its accuracy).
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+// amat[((l * 49 + o) * R + r) * R + k], R = 2(p+1) rounded up to 16.
+__global__ void m2l_amat_kernel(int depth, int p, int R, const double2* __restrict__ ts,
+                                double* __restrict__ amat) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= (int64_t)(depth + 1) * 49 * R) return;
+  const int r = (int)(t % R);
+  const int lo = (int)(t / R);   // l * 49 + o
+  const int K = 4 * p + 1, P1 = p + 1;
+  const double2* T = ts + (int64_t)lo * K + 2 * p;
+  double* row = amat + t * R;
+  for (int k = 0; k < R; ++k) {
+    double v = 0.0;
+    if (r < 2 * P1 && k < 2 * P1) {
+      const int m = r < P1 ? r : r - P1;
+      const int n = k < P1 ? k : k - P1;
+      const double sg = (m & 1) ? -1.0 : 1.0;
+      const double2 t1 = T[n - m];
+      const double2 t2 = n > 0 ? T[-n - m] : make_double2(0.0, 0.0);
+      if (r < P1)   // Re L_m
+        v = k < P1 ? t1.x + t2.x : -t1.y + t2.y;
+      else          // Im L_m
+        v = k < P1 ? t1.y + t2.y : t1.x - t2.x;
+      v *= sg;
+    }
+    row[k] = v;
+  }
+}
+
+template <int RT>
+__global__ __launch_bounds__(256) void m2l_mfma_kernel(int p, int nbox, const int* __restrict__ ild,
+                                                       const double2* __restrict__ M,
+                                                       const double* __restrict__ amat,
+                                                       double2* __restrict__ L) {
+  constexpr int R = RT * 16;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int t0 = (blockIdx.x * 4 + wave) * 16;
+  if (t0 >= nbox) return;                       // whole wave
+  const int P1 = p + 1;
+  const int col = lane & 15, kk = lane >> 4;
+  const int tb = t0 + col;
+  dbl4 acc[RT];
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt) acc[rt] = dbl4{0.0, 0.0, 0.0, 0.0};
+  for (int o = 0; o < 49; ++o) {
+    const int ox = o / 7 - 3, oy = o % 7 - 3;
+    if (ox >= -1 && ox <= 1 && oy >= -1 && oy <= 1) continue;
+    const int src = tb < nbox ? ild[(int64_t)tb * 49 + o] : -1;
+    if (__ballot(src >= 0) == 0) continue;      // no target of this wave has a source here
+    const double* A = amat + (int64_t)o * R * R;
+    for (int ks = 0; ks < R / 4; ++ks) {
+      const int k = ks * 4 + kk;
+      double bv = 0.0;
+      if (src >= 0 && k < 2 * P1) {
+        const double2 mv = M[(int64_t)src * P1 + (k < P1 ? k : k - P1)];
+        bv = k < P1 ? mv.x : mv.y;
+      }
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt) {
+        const double av = A[(int64_t)(rt * 16 + col) * R + k];
+        acc[rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[rt], 0, 0, 0);
+      }
+    }
+  }
+  if (tb >= nbox) return;
+  // FP64 16x16 result layout: lane l holds column l % 16, its register j row 4 j + l / 16
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int r = rt * 16 + 4 * j + kk;
+      if (r < P1)
+        L[(int64_t)tb * P1 + r].x = acc[rt][j];
+      else if (r < 2 * P1)
+        L[(int64_t)tb * P1 + r - P1].y = acc[rt][j];
+    }
+}
+
 // L2L: child level lc from parents (table level lc), accumulated.
 __global__ void l2l_kernel(int p, int nbox, const int* __restrict__ parent, const int* __restrict__ cpos,
                            const double2* __restrict__ Lp, const double2* __restrict__ tgl,
@@ -353,9 +441,38 @@ static inline void unmorton(int64_t k, int64_t& ix, int64_t& iy) {
 template <class T>
 static void up(DevBuf<T>& d, const std::vector<T>& h, hipStream_t s) {
   d.alloc(std::max<size_t>(h.size(), 1));
-  if (!h.empty())
+  if (!h.empty()) {
+    // the host vector is usually a temporary: wait for the copy
     YQ_HIP(hipMemcpyAsync(d.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    YQ_HIP(hipStreamSynchronize(s));
+  }
 }
+
+// Lookup of occupied boxes by grid position at one level: a dense table while the
+// level's grid is small, a hash map above that.
+struct BoxIndex {
+  int l = 0;
+  std::vector<int> dense;
+  std::unordered_map<int64_t, int> sparse;
+  void init(int level, const std::vector<int64_t>& keys) {
+    l = level;
+    const int64_t cells = 1LL << (2 * level);
+    dense.clear();
+    sparse.clear();
+    if (cells <= (1LL << 24)) {
+      dense.assign((size_t)cells, -1);
+      for (size_t b = 0; b < keys.size(); ++b) dense[(size_t)keys[b]] = (int)b;
+    } else {
+      sparse.reserve(keys.size() * 2);
+      for (size_t b = 0; b < keys.size(); ++b) sparse[keys[b]] = (int)b;
+    }
+  }
+  int find(int64_t key) const {
+    if (!dense.empty()) return key >= 0 && key < (int64_t)dense.size() ? dense[(size_t)key] : -1;
+    auto it = sparse.find(key);
+    return it == sparse.end() ? -1 : it->second;
+  }
+};
 
 void Fmm::build(const double* dx, const double* dy, const double* dwnx, const double* dwny, int64_t n,
                 double kap, int order, int lmax, const double* tab, hipStream_t s) {
@@ -381,39 +498,47 @@ void Fmm::build(const double* dx, const double* dy, const double* dwnx, const do
   W = std::max(xmax - xmin, ymax - ymin) * (1.0 + 1e-9) + 1e-12;
   x0 = 0.5 * (xmin + xmax) - 0.5 * W;
   y0 = 0.5 * (ymin + ymax) - 0.5 * W;
-  auto keys_at = [&](int d, std::vector<int64_t>& k) {
-    const int64_t m = 1LL << d;
-    k.resize(n);
+  // Morton keys at the finest candidate depth, sorted once; a coarser level's key
+  // is a right shift, so its occupancy is a linear scan of the sorted keys.
+  constexpr int DMAX = 14;
+  std::vector<int64_t> kmax(n);
+  {
+    const int64_t m = 1LL << DMAX;
     for (int64_t i = 0; i < n; ++i) {
       int64_t ix = (int64_t)((hx[i] - x0) / W * m), iy = (int64_t)((hy[i] - y0) / W * m);
       ix = std::min(std::max(ix, (int64_t)0), m - 1);
       iy = std::min(std::max(iy, (int64_t)0), m - 1);
-      k[i] = morton(ix, iy);
+      kmax[i] = morton(ix, iy);
     }
-  };
-  // depth: the shallowest with at most leaf_max nodes per occupied leaf on average
-  std::vector<int64_t> key;
-  depth = 2;
-  for (int d = 2; d <= 14; ++d) {
-    keys_at(d, key);
-    std::vector<int64_t> u(key);
-    std::sort(u.begin(), u.end());
-    const int64_t occ = std::unique(u.begin(), u.end()) - u.begin();
-    depth = d;
-    if ((double)n / occ <= (double)leaf_max) break;
   }
-  keys_at(depth, key);
   std::vector<int> order_idx(n);
   std::iota(order_idx.begin(), order_idx.end(), 0);
   std::stable_sort(order_idx.begin(), order_idx.end(),
-                   [&](int a, int b) { return key[a] < key[b]; });
+                   [&](int a, int b) { return kmax[a] < kmax[b]; });
+  depth = DMAX;
+  for (int d = 2; d <= DMAX; ++d) {
+    const int sh = 2 * (DMAX - d);
+    int64_t occ = 0, last = -1;
+    for (int64_t k = 0; k < n; ++k) {
+      const int64_t kk = kmax[order_idx[k]] >> sh;
+      if (kk != last) {
+        ++occ;
+        last = kk;
+      }
+    }
+    if ((double)n / occ <= (double)leaf_max) {
+      depth = d;
+      break;
+    }
+  }
+  const int shl = 2 * (DMAX - depth);
   lv.clear();
   lv.resize(depth + 1);
   std::vector<int> hls, hlc;
   {
     FmmLevel& L = lv[depth];
     for (int64_t k = 0; k < n; ++k) {
-      const int64_t kk = key[order_idx[k]];
+      const int64_t kk = kmax[order_idx[k]] >> shl;
       if (L.key.empty() || L.key.back() != kk) {
         L.key.push_back(kk);
         hls.push_back((int)k);
@@ -430,12 +555,12 @@ void Fmm::build(const double* dx, const double* dy, const double* dwnx, const do
     }
   }
   max_leaf = *std::max_element(hlc.begin(), hlc.end());
-  std::vector<std::unordered_map<int64_t, int>> idx(depth + 1);
+  std::vector<BoxIndex> idx(depth + 1);
   for (int l = 0; l <= depth; ++l) {
     FmmLevel& L = lv[l];
     L.nbox = (int)L.key.size();
     L.w = W / (double)(1LL << l);
-    for (int b = 0; b < L.nbox; ++b) idx[l][L.key[b]] = b;
+    idx[l].init(l, L.key);
   }
   std::vector<int> hnbp(1, 0), hnbi;
   for (int l = 0; l <= depth; ++l) {
@@ -449,41 +574,40 @@ void Fmm::build(const double* dx, const double* dy, const double* dwnx, const do
       hcx[b] = x0 + (ix + 0.5) * L.w;
       hcy[b] = y0 + (iy + 0.5) * L.w;
       if (l > 0) {
-        hpar[b] = idx[l - 1].at(L.key[b] >> 2);
+        hpar[b] = idx[l - 1].find(L.key[b] >> 2);
         hpos[b] = (int)(L.key[b] & 3);
       }
       if (l < depth)
-        for (int pos = 0; pos < 4; ++pos) {
-          auto it = idx[l + 1].find((L.key[b] << 2) | pos);
-          if (it != idx[l + 1].end()) hch[4 * (size_t)b + pos] = it->second;
-        }
+        for (int pos = 0; pos < 4; ++pos) hch[4 * (size_t)b + pos] = idx[l + 1].find((L.key[b] << 2) | pos);
       if (l >= 2) {
         int64_t px, py;
         unmorton(L.key[b] >> 2, px, py);
+        const int64_t lim = 1LL << (l - 1);
         for (int ddx = -1; ddx <= 1; ++ddx)
           for (int ddy = -1; ddy <= 1; ++ddy) {
-            if (px + ddx < 0 || py + ddy < 0) continue;
-            auto pit = idx[l - 1].find(morton(px + ddx, py + ddy));
-            if (pit == idx[l - 1].end()) continue;
+            if (px + ddx < 0 || py + ddy < 0 || px + ddx >= lim || py + ddy >= lim) continue;
+            const int pb = idx[l - 1].find(morton(px + ddx, py + ddy));
+            if (pb < 0) continue;
             for (int pos = 0; pos < 4; ++pos) {
-              auto sit = idx[l].find((lv[l - 1].key[pit->second] << 2) | pos);
-              if (sit == idx[l].end()) continue;
+              const int sb = idx[l].find((lv[l - 1].key[pb] << 2) | pos);
+              if (sb < 0) continue;
               int64_t sx, sy;
-              unmorton(lv[l].key[sit->second], sx, sy);
+              unmorton(lv[l].key[sb], sx, sy);
               const int64_t ox = sx - ix, oy = sy - iy;
               if (std::llabs(ox) <= 1 && std::llabs(oy) <= 1) continue;
-              ils.push_back(sit->second);
+              ils.push_back(sb);
               ilo.push_back((int)((ox + 3) * 7 + (oy + 3)));
             }
           }
         ilp.push_back((int)ils.size());
       }
       if (l == depth) {
+        const int64_t lim = 1LL << l;
         for (int ddx = -1; ddx <= 1; ++ddx)
           for (int ddy = -1; ddy <= 1; ++ddy) {
-            if (ix + ddx < 0 || iy + ddy < 0) continue;
-            auto nit = idx[l].find(morton(ix + ddx, iy + ddy));
-            if (nit != idx[l].end()) hnbi.push_back(nit->second);
+            if (ix + ddx < 0 || iy + ddy < 0 || ix + ddx >= lim || iy + ddy >= lim) continue;
+            const int nb = idx[l].find(morton(ix + ddx, iy + ddy));
+            if (nb >= 0) hnbi.push_back(nb);
           }
         hnbp.push_back((int)hnbi.size());
       }
@@ -497,15 +621,16 @@ void Fmm::build(const double* dx, const double* dy, const double* dwnx, const do
       up(L.ilp, ilp, s);
       up(L.ils, ils, s);
       up(L.ilo, ilo, s);
+      std::vector<int> dense((size_t)L.nbox * 49, -1);
+      for (int b = 0; b < L.nbox; ++b)
+        for (int e = ilp[b]; e < ilp[b + 1]; ++e) dense[(size_t)b * 49 + ilo[e]] = ils[e];
+      up(L.ild, dense, s);
     }
-    L.M.alloc((size_t)L.nbox * (p + 1));
-    L.L.alloc((size_t)L.nbox * (p + 1));
   }
   up(leaf_start, hls, s);
   up(leaf_cnt, hlc, s);
   up(nbp, hnbp, s);
   up(nbi, hnbi, s);
-  std::vector<int> hperm(order_idx);
   std::vector<double> sx(n), sy(n), swx(n), swy(n);
   for (int64_t k = 0; k < n; ++k) {
     const int i = order_idx[k];
@@ -514,21 +639,86 @@ void Fmm::build(const double* dx, const double* dy, const double* dwnx, const do
     swx[k] = hwx[i];
     swy[k] = hwy[i];
   }
-  up(perm, hperm, s);
+  up(perm, order_idx, s);
   up(xs, sx, s);
   up(ys, sy, s);
   up(wnxs, swx, s);
   up(wnys, swy, s);
   qx.alloc(n);
   qy.alloc(n);
+  set_order(order, tab, s);
+}
+
+// (Re)allocates the expansions and builds the translation tables for order q.
+void Fmm::set_order(int q, const double* tab, hipStream_t s) {
+  YQ_REQUIRE(q >= 1 && q <= MAXP_FMM, YQ_EINVAL, "FMM order must be in 1..48");
+  p = q;
+  for (auto& L : lv) {
+    L.M.alloc((size_t)std::max(L.nbox, 1) * (p + 1));
+    L.L.alloc((size_t)std::max(L.nbox, 1) * (p + 1));
+  }
   const int K = 4 * p + 1;
   tg.alloc((size_t)(depth + 1) * 4 * K);
   ts.alloc((size_t)(depth + 1) * 49 * K);
   tab_g_kernel<<<((depth + 1) * 4 + 63) / 64, 64, 0, s>>>(depth, p, W, kappa, tg.p);
   tab_s_kernel<<<((depth + 1) * 49 + 63) / 64, 64, 0, s>>>(depth, p, W, kappa, tab, ts.p);
   YQ_HIP(hipGetLastError());
+  R16 = ((2 * (p + 1) + 15) / 16) * 16;
+  if (use_mfma) {
+    const int64_t rows = (int64_t)(depth + 1) * 49 * R16;
+    amat.alloc((size_t)rows * R16);
+    m2l_amat_kernel<<<(unsigned)((rows + 127) / 128), 128, 0, s>>>(depth, p, R16, ts.p, amat.p);
+    YQ_HIP(hipGetLastError());
+  }
   YQ_HIP(hipStreamSynchronize(s));
   built = true;
+}
+
+// A second expansion order on the same tree: copies the tree (device to device).
+void Fmm::copy_tree(const Fmm& o, int q, const double* tab, hipStream_t s) {
+  auto dup = [&](auto& dst, const auto& src) {
+    using T = std::remove_pointer_t<decltype(src.p)>;
+    dst.alloc(std::max<size_t>(src.n, 1));
+    if (src.n) YQ_HIP(hipMemcpyAsync(dst.p, src.p, src.n * sizeof(T), hipMemcpyDeviceToDevice, s));
+  };
+  depth = o.depth;
+  leaf_max = o.leaf_max;
+  x0 = o.x0;
+  y0 = o.y0;
+  W = o.W;
+  kappa = o.kappa;
+  N = o.N;
+  max_leaf = o.max_leaf;
+  lv.clear();
+  lv.resize(o.lv.size());
+  for (size_t l = 0; l < o.lv.size(); ++l) {
+    lv[l].nbox = o.lv[l].nbox;
+    lv[l].w = o.lv[l].w;
+    lv[l].key = o.lv[l].key;
+    dup(lv[l].cx, o.lv[l].cx);
+    dup(lv[l].cy, o.lv[l].cy);
+    dup(lv[l].parent, o.lv[l].parent);
+    dup(lv[l].cpos, o.lv[l].cpos);
+    dup(lv[l].ch, o.lv[l].ch);
+    if (l >= 2) {
+      dup(lv[l].ilp, o.lv[l].ilp);
+      dup(lv[l].ils, o.lv[l].ils);
+      dup(lv[l].ilo, o.lv[l].ilo);
+      dup(lv[l].ild, o.lv[l].ild);
+    }
+  }
+  dup(perm, o.perm);
+  dup(xs, o.xs);
+  dup(ys, o.ys);
+  dup(wnxs, o.wnxs);
+  dup(wnys, o.wnys);
+  dup(leaf_start, o.leaf_start);
+  dup(leaf_cnt, o.leaf_cnt);
+  dup(nbp, o.nbp);
+  dup(nbi, o.nbi);
+  qx.alloc(N);
+  qy.alloc(N);
+  set_order(q, tab, s);
 }
 
 void Fmm::apply(const double* sigma, double* partial, bool p2p_fp32, const double* tab,
@@ -549,10 +739,25 @@ void Fmm::apply(const double* sigma, double* partial, bool p2p_fp32, const doubl
                                                             lv[l].M.p);
   }
   for (int l = 2; l <= depth; ++l) {
-    const int64_t nt = (int64_t)lv[l].nbox * (p + 1);
-    m2l_kernel<<<(unsigned)((nt + 127) / 128), 128, 0, s>>>(p, lv[l].nbox, lv[l].ilp.p, lv[l].ils.p,
-                                                            lv[l].ilo.p, lv[l].M.p,
-                                                            ts.p + (size_t)l * 49 * K, lv[l].L.p);
+    const int nb = lv[l].nbox;
+    if (use_mfma) {
+      const double* A = amat.p + (size_t)l * 49 * R16 * R16;
+      const unsigned g = (unsigned)((nb + 63) / 64);
+      switch (R16 / 16) {
+        case 1: m2l_mfma_kernel<1><<<g, 256, 0, s>>>(p, nb, lv[l].ild.p, lv[l].M.p, A, lv[l].L.p); break;
+        case 2: m2l_mfma_kernel<2><<<g, 256, 0, s>>>(p, nb, lv[l].ild.p, lv[l].M.p, A, lv[l].L.p); break;
+        case 3: m2l_mfma_kernel<3><<<g, 256, 0, s>>>(p, nb, lv[l].ild.p, lv[l].M.p, A, lv[l].L.p); break;
+        case 4: m2l_mfma_kernel<4><<<g, 256, 0, s>>>(p, nb, lv[l].ild.p, lv[l].M.p, A, lv[l].L.p); break;
+        case 5: m2l_mfma_kernel<5><<<g, 256, 0, s>>>(p, nb, lv[l].ild.p, lv[l].M.p, A, lv[l].L.p); break;
+        case 6: m2l_mfma_kernel<6><<<g, 256, 0, s>>>(p, nb, lv[l].ild.p, lv[l].M.p, A, lv[l].L.p); break;
+        default: m2l_mfma_kernel<7><<<g, 256, 0, s>>>(p, nb, lv[l].ild.p, lv[l].M.p, A, lv[l].L.p); break;
+      }
+    } else {
+      const int64_t nt = (int64_t)nb * (p + 1);
+      m2l_kernel<<<(unsigned)((nt + 127) / 128), 128, 0, s>>>(p, nb, lv[l].ilp.p, lv[l].ils.p,
+                                                              lv[l].ilo.p, lv[l].M.p,
+                                                              ts.p + (size_t)l * 49 * K, lv[l].L.p);
+    }
   }
   for (int l = 2; l < depth; ++l) {
     const int64_t nt = (int64_t)lv[l + 1].nbox * (p + 1);

@@ -50,6 +50,9 @@ def test_default_params_and_error_strings():
     assert lib.yq_create(ctypes.byref(bad), ctypes.byref(h)) == _lib.YQ_EINVAL
     bad = yq.default_params(panels_per_particle=4)
     assert lib.yq_create(ctypes.byref(bad), ctypes.byref(h)) == _lib.YQ_EINVAL
+    assert p.fmm_resid_order == 40 and p.fmm_m2l == yq.YQ_M2L_MFMA
+    bad = yq.default_params(fmm_m2l=7)
+    assert lib.yq_create(ctypes.byref(bad), ctypes.byref(h)) == _lib.YQ_EINVAL
 
 
 def test_gauss_tables_generator_matches_header():
@@ -60,3 +63,17 @@ def test_gauss_tables_generator_matches_header():
     out = subprocess.run([sys.executable, gen], capture_output=True, text=True, check=True).stdout
     hdr = open(os.path.join(ROOT, "paper_1810_04131_amd", "csrc", "bessel_tables.h")).read()
     assert out.strip() == hdr.strip()
+
+
+def test_library_shares_torch_hip_runtime():
+    # loading the library before torch must not map a second HIP runtime
+    import subprocess
+    import sys
+    from paper_1810_04131_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("libyqbx.so not built")
+    code = ("import paper_1810_04131_amd._lib as L; L.load(); import torch; "
+            "print(sorted({l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l}))")
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, check=True,
+                         cwd=ROOT).stdout
+    assert out.count("libamdhip64") == 1, out

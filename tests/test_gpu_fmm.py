@@ -48,6 +48,22 @@ def test_fmm_converges_to_direct_far_field(medium):
     assert errs[20] < 1e-5 and errs[26] < 1e-6, errs
 
 
+@pytest.mark.parametrize("order", [5, 20, 48])
+def test_fmm_m2l_matrix_cores_match_vector_alu(medium, order):
+    # the M2L on FP64 MFMA tiles and the per-coefficient VALU kernel compute the
+    # same sums in a different order: they agree to rounding at every tile count
+    _torch()
+    parts = medium["particles"]
+    sig = workloads.random_density(25600, 6)
+    out = {}
+    for m2l in (yq.YQ_M2L_MFMA, yq.YQ_M2L_VALU):
+        pb = yq.Problem(yq.default_params(far_mode=yq.YQ_FAR_FMM, fmm_order=order, fmm_leaf_max=64,
+                                          fmm_m2l=m2l))
+        pb.set_workload(parts)
+        out[m2l] = _np(pb.apply_far(sig, yq.YQ_FMM64))
+    assert _rel(out[yq.YQ_M2L_MFMA], out[yq.YQ_M2L_VALU]) < 1e-12
+
+
 def test_fmm_far_field_against_oracle_rows(medium):
     _torch()
     parts = medium["particles"]
