@@ -82,8 +82,9 @@ typedef struct yq_params {
   int32_t fmm_resid_order;     /* FMM enabled: order of the FP64 FMM used for refinement residuals,
                                   FP64 solves and the reported residual (relative operator error
                                   ~1e-10 at 40); 0 = the exact direct sum */
-  int32_t fmm_m2l;             /* FMM M2L translations: YQ_M2L_MFMA (FP64 matrix-core products)
-                                  or YQ_M2L_VALU (one lane per coefficient); same results to rounding */
+  int32_t fmm_m2l;             /* FMM M2M/M2L/L2L translations: YQ_M2L_MFMA (FP64 matrix-core
+                                  products) or YQ_M2L_VALU (one lane per coefficient); the same
+                                  results to rounding */
 } yq_params;
 
 typedef struct yq_solve_info {

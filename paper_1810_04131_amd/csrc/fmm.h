@@ -35,15 +35,20 @@ struct Fmm {
   DevBuf<double2> ts;  // M2L tables: [level][offset 0..48][k + 2p]
   int max_leaf = 0;
   bool built = false;
-  bool use_mfma = true;   // M2L on the matrix cores (FP64 MFMA)
+  bool use_mfma = true;   // M2M, M2L, L2L on the matrix cores (FP64 MFMA)
   int R16 = 0;            // 2 (p + 1) rounded up to a multiple of 16
-  DevBuf<double> amat;    // M2L matrices [level][offset][R16][R16]
+  DevBuf<double> amat;    // M2L matrices [level][offset][R16 * R16] in MFMA operand order
+  DevBuf<double> gmat;    // M2M / L2L matrices [level][child position][R16 * R16], same order
+  DevBuf<int2> m2l_tiles; // (level, first box) of every 16-box M2L tile
+  int n_m2l_tiles = 0;
 
   void build(const double* dx, const double* dy, const double* dwnx, const double* dwny,
              int64_t n, double kappa, int order, int leaf_max, const double* tab, hipStream_t s);
   void set_order(int q, const double* tab, hipStream_t s);
   void copy_tree(const Fmm& o, int q, const double* tab, hipStream_t s);
   // partial[i] = (2 pi / kappa^2) * far field at node i (the far-field kernels' scaling)
+  void m2l_mfma(hipStream_t s);
+  void tree_mfma(bool gather, int l, hipStream_t s);
   void apply(const double* sigma, double* partial, bool p2p_fp32, const double* tab,
              hipStream_t s);
 };

@@ -24,6 +24,7 @@
 // device.
 #include <algorithm>
 #include <cmath>
+#include <memory>
 #include <numeric>
 #include <type_traits>
 #include <unordered_map>
@@ -43,20 +44,33 @@ __device__ __forceinline__ double2 cmad(double2 a, double2 b, double2 c) {
 }
 __device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
 
-// I_k(x), k = 0..n, by the ascending series; I[k * stride].
+// I_k(x) for one order k by the ascending series, from pref = (x/2)^k / k! and
+// t = x^2 / 4 (all terms positive; reciprocals instead of divisions).
+__device__ __forceinline__ double iorder(double t, double pref, int k) {
+  double term = pref, sum = pref;
+  for (int j = 1; j < 400; ++j) {
+    term *= t * rcp64(double(j) * double(k + j));
+    sum += term;
+    if (term <= 1e-17 * sum) break;
+  }
+  return sum;
+}
+
+// I_k(x), k = 0..n; I[k * stride].
 __device__ inline void iseries(double x, int n, double* I, int stride) {
   const double t = 0.25 * x * x;
   double pref = 1.0;
   for (int k = 0; k <= n; ++k) {
-    double term = pref, sum = pref;
-    for (int j = 1; j < 400; ++j) {
-      term *= t / (double(j) * double(k + j));
-      sum += term;
-      if (term <= 1e-17 * sum) break;
-    }
-    I[(int64_t)k * stride] = sum;
-    pref *= 0.5 * x / double(k + 1);
+    I[(int64_t)k * stride] = iorder(t, pref, k);
+    pref *= 0.5 * x * rcp64(double(k + 1));
   }
+}
+
+// Sum over the 64 lanes of a wave (fixed butterfly order: the same bits on every run).
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
 }
 
 // ---- translation tables ------------------------------------------------------------------
@@ -131,9 +145,10 @@ __global__ void gather_kernel(int64_t N, const int* __restrict__ perm, const dou
 
 constexpr int FB = 64;
 
-// One block per leaf (blockDim.x threads, LDS scaled to it): multipole
-// coefficients M_n, n = 0..p.
-__global__ __launch_bounds__(FB) void p2m_kernel(int p, double kappa, const int* __restrict__ ls,
+// One wave per leaf: multipole coefficients M_n, n = 0..p.  A lane takes one
+// node at a time, rolls I_{n-1}, I_n, I_{n+1} and e^{i(n +- 1) phi} along n, and
+// the wave sums each coefficient; lane n keeps M_n.
+__global__ __launch_bounds__(64) void p2m_kernel(int p, double kappa, const int* __restrict__ ls,
                                                  const int* __restrict__ lc,
                                                  const double* __restrict__ ccx,
                                                  const double* __restrict__ ccy,
@@ -142,56 +157,50 @@ __global__ __launch_bounds__(FB) void p2m_kernel(int p, double kappa, const int*
                                                  const double* __restrict__ qx,
                                                  const double* __restrict__ qy,
                                                  double2* __restrict__ M) {
-  extern __shared__ double sh[];
-  const int tid = threadIdx.x;
-  const int B = blockDim.x;
+  const int lane = threadIdx.x;
   const int b = blockIdx.x;
-  double* I = sh;                      // [(p + 2) * B]
-  double* acc = sh + (p + 2) * B;      // [2 (p + 1) * B]
-  for (int n = 0; n <= p; ++n) {
-    acc[(2 * n) * B + tid] = 0.0;
-    acc[(2 * n + 1) * B + tid] = 0.0;
-  }
   const int s0 = ls[b], cnt = lc[b];
   const double cx = ccx[b], cy = ccy[b];
-  for (int j = tid; j < cnt; j += B) {
-    const double dx = xs[s0 + j] - cx, dy = ys[s0 + j] - cy;
+  double2 mine = make_double2(0.0, 0.0);
+  for (int r0 = 0; r0 < cnt; r0 += 64) {
+    const int j = r0 + lane;
+    double dx = 0.0, dy = 0.0;
+    double2 Q = make_double2(0.0, 0.0);
+    if (j < cnt) {
+      dx = xs[s0 + j] - cx;
+      dy = ys[s0 + j] - cy;
+      Q = make_double2(qx[s0 + j], qy[s0 + j]);
+    }
     const double rho = sqrt(dx * dx + dy * dy);
-    iseries(kappa * rho, p + 1, I + tid, B);
+    const double x = kappa * rho, t = 0.25 * x * x, hx = 0.5 * x;
     const double2 e1 = rho > 0.0 ? make_double2(dx / rho, dy / rho) : make_double2(1.0, 0.0);
-    const double2 Q = make_double2(qx[s0 + j], qy[s0 + j]);
     const double2 Qc = cconj(Q);
-    double2 Em = cconj(e1), Ep = e1;  // e^{i(n-1)phi}, e^{i(n+1)phi} at n = 0
+    double pref = hx;                               // (x/2)^{n+1} / (n+1)!
+    double Im = 0.0, I0 = iorder(t, 1.0, 0), Ip = iorder(t, pref, 1);
+    double2 Em = cconj(e1), Ep = e1;                // e^{i(n-1)phi}, e^{i(n+1)phi}
     for (int n = 0; n <= p; ++n) {
-      double2 gm;
-      if (n == 0) {
-        const double i1 = I[1 * B + tid];
-        gm = make_double2(i1 * e1.x, i1 * e1.y);                    // g_1
-      } else {
-        const double im = I[(n - 1) * B + tid];
-        gm = make_double2(im * Em.x, -im * Em.y);                  // conj(g_{n-1})
+      const double2 gm = n == 0 ? make_double2(Ip * e1.x, Ip * e1.y)     // g_1
+                                : make_double2(Im * Em.x, -Im * Em.y);   // conj(g_{n-1})
+      const double2 gp = make_double2(Ip * Ep.x, -Ip * Ep.y);            // conj(g_{n+1})
+      double2 c = cmul(Qc, gm);
+      c = cmad(Q, gp, c);
+      c.x = wave_sum(c.x);
+      c.y = wave_sum(c.y);
+      if (lane == n) {
+        mine.x += c.x;
+        mine.y += c.y;
       }
-      const double ip = I[(n + 1) * B + tid];
-      const double2 gp = make_double2(ip * Ep.x, -ip * Ep.y);     // conj(g_{n+1})
-      double2 a = make_double2(acc[(2 * n) * B + tid], acc[(2 * n + 1) * B + tid]);
-      a = cmad(Qc, gm, a);
-      a = cmad(Q, gp, a);
-      acc[(2 * n) * B + tid] = a.x;
-      acc[(2 * n + 1) * B + tid] = a.y;
+      pref *= hx * rcp64(double(n + 2));
+      Im = I0;
+      I0 = Ip;
+      Ip = iorder(t, pref, n + 2);
       Em = (n == 0) ? make_double2(1.0, 0.0) : cmul(Em, e1);
       Ep = cmul(Ep, e1);
     }
   }
-  __syncthreads();
-  const double sc = kappa / (4.0 * PI);
-  for (int v = tid; v < 2 * (p + 1); v += B) {
-    double s = 0.0;
-    for (int t = 0; t < B; ++t) s += acc[v * B + t];
-    const int n = v >> 1;
-    if (v & 1)
-      M[(int64_t)b * (p + 1) + n].y = s * sc;
-    else
-      M[(int64_t)b * (p + 1) + n].x = s * sc;
+  if (lane <= p) {
+    const double sc = kappa / (4.0 * PI);
+    M[(int64_t)b * (p + 1) + lane] = make_double2(mine.x * sc, mine.y * sc);
   }
 }
 
@@ -241,87 +250,188 @@ __global__ void m2l_kernel(int p, int nbox, const int* __restrict__ ilp, const i
 //
 // With x = (Re M_0..Re M_p, Im M_0..Im M_p) and y likewise for L, one M2L term
 // is y += A_o x, A_o a real 2(p+1) x 2(p+1) matrix per (level, offset) that
-// carries (-1)^m and the M_{-n} = conj(M_n) fold.  A wave computes 16 target
-// boxes at once: for every offset, B = the 16 gathered source vectors (zero
-// where a target has no source at that offset), D += A_o B with
-// v_mfma_f64_16x16x4f64 tiles (FP64, so the FMM keeps its accuracy).
+// carries (-1)^m and the M_{-n} = conj(M_n) fold (rows and columns padded to
+// R, a multiple of 16).  A wave owns one 16 x 16 output tile: 16 rows of y
+// for 16 consecutive target boxes of one level.  For every far offset it
+// gathers the 16 source vectors (zero where a target has none there) and
+// accumulates A_o B with v_mfma_f64_16x16x4f64 (FP64, so the FMM keeps its
+// accuracy).  All levels go in one launch: their M2L terms are independent.
 typedef double dbl4 __attribute__((ext_vector_type(4)));
+constexpr int DMAX = 14;   // deepest quadtree level
 
-// amat[((l * 49 + o) * R + r) * R + k], R = 2(p+1) rounded up to 16.
-__global__ void m2l_amat_kernel(int depth, int p, int R, const double2* __restrict__ ts,
-                                double* __restrict__ amat) {
+// Translation matrices in the operand order of the 16x16x4 product: for
+// (level, slot, row tile rt, k step ks) the 64 values lane by lane, lane =
+// i + 16 kk holding A[16 rt + i][4 ks + kk], so that a wave's operand load is
+// one coalesced row.  A slot is an M2L offset (49 per level, table ts, sign
+// (-1)^m) or a child position (4 per level, table tg, no sign; M2M and L2L
+// use the same matrices).
+__global__ void trans_amat_kernel(int nlev, int nslot, int p, int R, int alt_sign,
+                                  const double2* __restrict__ tab, double* __restrict__ amat) {
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (t >= (int64_t)(depth + 1) * 49 * R) return;
-  const int r = (int)(t % R);
-  const int lo = (int)(t / R);   // l * 49 + o
-  const int K = 4 * p + 1, P1 = p + 1;
-  const double2* T = ts + (int64_t)lo * K + 2 * p;
-  double* row = amat + t * R;
-  for (int k = 0; k < R; ++k) {
-    double v = 0.0;
-    if (r < 2 * P1 && k < 2 * P1) {
-      const int m = r < P1 ? r : r - P1;
-      const int n = k < P1 ? k : k - P1;
-      const double sg = (m & 1) ? -1.0 : 1.0;
-      const double2 t1 = T[n - m];
-      const double2 t2 = n > 0 ? T[-n - m] : make_double2(0.0, 0.0);
-      if (r < P1)   // Re L_m
-        v = k < P1 ? t1.x + t2.x : -t1.y + t2.y;
-      else          // Im L_m
-        v = k < P1 ? t1.y + t2.y : t1.x - t2.x;
-      v *= sg;
+  const int64_t per = (int64_t)R * R;        // values per (level, slot)
+  if (t >= (int64_t)nlev * nslot * per) return;
+  const int64_t lo = t / per;                // level * nslot + slot
+  const int rem = (int)(t % per);
+  const int lane = rem & 63, tile = rem >> 6;          // tile = rt * (R / 4) + ks
+  const int rt = tile / (R / 4), ks = tile % (R / 4);
+  const int r = 16 * rt + (lane & 15), k = 4 * ks + (lane >> 4);
+  const int P1 = p + 1;
+  double v = 0.0;
+  if (r < 2 * P1 && k < 2 * P1) {
+    const double2* T = tab + lo * (4 * p + 1) + 2 * p;
+    const int m = r < P1 ? r : r - P1;
+    const int n = k < P1 ? k : k - P1;
+    const double2 t1 = T[n - m];
+    const double2 t2 = n > 0 ? T[-n - m] : make_double2(0.0, 0.0);
+    if (r < P1)   // Re y_m
+      v = k < P1 ? t1.x + t2.x : -t1.y + t2.y;
+    else          // Im y_m
+      v = k < P1 ? t1.y + t2.y : t1.x - t2.x;
+    if (alt_sign && (m & 1)) v = -v;
+  }
+  amat[t] = v;
+}
+
+// Operands of one 16x16 result tile (A rows, source columns) for KS k steps.
+template <int KS>
+struct TileOps {
+  double a[KS], b[KS];
+};
+
+// Loads the operands: A from its operand-ordered rows, B from the source box's
+// coefficients (ms == nullptr: a zero column).
+template <int KS>
+__device__ __forceinline__ void tile_load(TileOps<KS>& op, const double* __restrict__ A,
+                                          const double2* __restrict__ ms, int P1, int kk) {
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) {
+    op.a[ks] = A[ks * 64];
+    const int k = 4 * ks + kk;
+    double b = 0.0;
+    if (ms != nullptr && k < 2 * P1) {
+      const double2 mv = ms[k < P1 ? k : k - P1];
+      b = k < P1 ? mv.x : mv.y;
     }
-    row[k] = v;
+    op.b[ks] = b;
   }
 }
 
+template <int KS>
+__device__ __forceinline__ dbl4 tile_mfma(const TileOps<KS>& op, dbl4 acc) {
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(op.a[ks], op.b[ks], acc, 0, 0, 0);
+  return acc;
+}
+
+// Writes (or adds) a result tile to box rows 16 rt .. 16 rt + 15 of y.
+// FP64 16x16 result layout: lane l holds column l % 16, its register j row 4 j + l / 16.
+template <bool ADD>
+__device__ __forceinline__ void tile_store(double2* __restrict__ y, int rt, int kk, int P1, dbl4 acc) {
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int r = rt * 16 + 4 * j + kk;
+    if (r < P1)
+      y[r].x = ADD ? y[r].x + acc[j] : acc[j];
+    else if (r < 2 * P1)
+      y[r - P1].y = ADD ? y[r - P1].y + acc[j] : acc[j];
+  }
+}
+
+// Sum of the four waves' tiles in a fixed order; the result is valid in wave 0.
+__device__ __forceinline__ dbl4 block_tile_sum(dbl4 acc, dbl4* red) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (wave > 0) red[(wave - 1) * 64 + lane] = acc;
+  __syncthreads();
+  if (wave == 0)
+    for (int w = 0; w < 3; ++w) acc += red[w * 64 + lane];
+  return acc;
+}
+
+// i-th of the 40 offsets (ox, oy) outside the 3 x 3 neighbourhood, as o = (ox+3) 7 + (oy+3).
+__device__ __forceinline__ int far_offset(int i) {
+  if (i < 14) return i;                                   // ox = -3, -2
+  if (i < 26) {                                           // ox = -1, 0, 1: oy = -3, -2, 2, 3
+    const int k = i - 14, c = k & 3;
+    return (2 + (k >> 2)) * 7 + (c < 2 ? c : c + 3);
+  }
+  return i + 9;                                           // ox = 2, 3
+}
+
+struct M2LLevels {
+  const int* ild[DMAX + 1];
+  const double2* M[DMAX + 1];
+  double2* L[DMAX + 1];
+  int nbox[DMAX + 1];
+};
+
+// One block (4 waves) per (16-box tile, row tile); wave w takes far offsets
+// w, w + 4, ..., loading the next offset's operands while the current one's
+// products run.
 template <int RT>
-__global__ __launch_bounds__(256) void m2l_mfma_kernel(int p, int nbox, const int* __restrict__ ild,
-                                                       const double2* __restrict__ M,
-                                                       const double* __restrict__ amat,
-                                                       double2* __restrict__ L) {
-  constexpr int R = RT * 16;
+__global__ __launch_bounds__(256) void m2l_mfma_kernel(int p, const int2* __restrict__ tiles,
+                                                       M2LLevels lv, const double* __restrict__ amat,
+                                                       int64_t level_stride) {
+  constexpr int R = RT * 16, KS = R / 4, NI = 10;
+  __shared__ dbl4 red[3 * 64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int t0 = (blockIdx.x * 4 + wave) * 16;
-  if (t0 >= nbox) return;                       // whole wave
+  const int2 tl = tiles[blockIdx.x / RT];       // (level, first box)
+  const int rt = blockIdx.x % RT;
+  const int l = tl.x, nbox = lv.nbox[l];
+  const int* __restrict__ ild = lv.ild[l];
+  const double2* __restrict__ M = lv.M[l];
   const int P1 = p + 1;
   const int col = lane & 15, kk = lane >> 4;
-  const int tb = t0 + col;
-  dbl4 acc[RT];
+  const int tb = tl.y + col;
+  const double* Al = amat + l * level_stride + (int64_t)rt * KS * 64 + lane;
+  int src[NI];
 #pragma unroll
-  for (int rt = 0; rt < RT; ++rt) acc[rt] = dbl4{0.0, 0.0, 0.0, 0.0};
-  for (int o = 0; o < 49; ++o) {
-    const int ox = o / 7 - 3, oy = o % 7 - 3;
-    if (ox >= -1 && ox <= 1 && oy >= -1 && oy <= 1) continue;
-    const int src = tb < nbox ? ild[(int64_t)tb * 49 + o] : -1;
-    if (__ballot(src >= 0) == 0) continue;      // no target of this wave has a source here
-    const double* A = amat + (int64_t)o * R * R;
-    for (int ks = 0; ks < R / 4; ++ks) {
-      const int k = ks * 4 + kk;
-      double bv = 0.0;
-      if (src >= 0 && k < 2 * P1) {
-        const double2 mv = M[(int64_t)src * P1 + (k < P1 ? k : k - P1)];
-        bv = k < P1 ? mv.x : mv.y;
-      }
+  for (int i = 0; i < NI; ++i) src[i] = tb < nbox ? ild[(int64_t)tb * 49 + far_offset(wave + 4 * i)] : -1;
+  auto A_of = [&](int i) { return Al + (int64_t)far_offset(wave + 4 * i) * R * R; };
+  auto M_of = [&](int i) { return src[i] >= 0 ? M + (int64_t)src[i] * P1 : nullptr; };
+  TileOps<KS> o0, o1;
+  dbl4 acc = dbl4{0.0, 0.0, 0.0, 0.0};
+  tile_load<KS>(o0, A_of(0), M_of(0), P1, kk);
 #pragma unroll
-      for (int rt = 0; rt < RT; ++rt) {
-        const double av = A[(int64_t)(rt * 16 + col) * R + k];
-        acc[rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[rt], 0, 0, 0);
-      }
-    }
+  for (int i = 0; i < NI; i += 2) {
+    tile_load<KS>(o1, A_of(i + 1), M_of(i + 1), P1, kk);
+    acc = tile_mfma<KS>(o0, acc);
+    if (i + 2 < NI) tile_load<KS>(o0, A_of(i + 2), M_of(i + 2), P1, kk);
+    acc = tile_mfma<KS>(o1, acc);
   }
-  if (tb >= nbox) return;
-  // FP64 16x16 result layout: lane l holds column l % 16, its register j row 4 j + l / 16
-#pragma unroll
-  for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int r = rt * 16 + 4 * j + kk;
-      if (r < P1)
-        L[(int64_t)tb * P1 + r].x = acc[rt][j];
-      else if (r < 2 * P1)
-        L[(int64_t)tb * P1 + r - P1].y = acc[rt][j];
-    }
+  acc = block_tile_sum(acc, red);
+  if (wave == 0 && tb < nbox) tile_store<false>(lv.L[l] + (int64_t)tb * P1, rt, kk, P1, acc);
+}
+
+// M2M (GATHER: parent tiles at level l, y = sum over the 4 children of A_pos x_child)
+// and L2L (scatter: parent tiles, child_pos += A_pos x_parent), one level per
+// launch, one block (4 waves, wave = child position) per (16-box tile, row
+// tile); A points at the child level's 4 matrices, ch is the children table.
+template <int RT, bool GATHER>
+__global__ __launch_bounds__(256) void tree_mfma_kernel(int p, int nbox, const int* __restrict__ ch,
+                                                        const double2* __restrict__ X,
+                                                        const double* __restrict__ amat,
+                                                        double2* __restrict__ Y) {
+  constexpr int R = RT * 16, KS = R / 4;
+  __shared__ dbl4 red[3 * 64];
+  const int lane = threadIdx.x & 63, pos = threadIdx.x >> 6;
+  const int rt = blockIdx.x % RT;
+  const int P1 = p + 1;
+  const int col = lane & 15, kk = lane >> 4;
+  const int tb = (blockIdx.x / RT) * 16 + col;
+  const double* A = amat + (int64_t)pos * R * R + (int64_t)rt * KS * 64 + lane;
+  const int c = tb < nbox ? ch[4 * (int64_t)tb + pos] : -1;
+  TileOps<KS> op;
+  if (GATHER) {
+    tile_load<KS>(op, A, c >= 0 ? X + (int64_t)c * P1 : nullptr, P1, kk);
+    dbl4 acc = tile_mfma<KS>(op, dbl4{0.0, 0.0, 0.0, 0.0});
+    acc = block_tile_sum(acc, red);
+    if (pos == 0 && tb < nbox) tile_store<false>(Y + (int64_t)tb * P1, rt, kk, P1, acc);
+  } else {
+    if (__ballot(c >= 0) == 0) return;          // whole wave: no child at this position
+    tile_load<KS>(op, A, tb < nbox ? X + (int64_t)tb * P1 : nullptr, P1, kk);
+    const dbl4 acc = tile_mfma<KS>(op, dbl4{0.0, 0.0, 0.0, 0.0});
+    if (c >= 0) tile_store<true>(Y + (int64_t)c * P1, rt, kk, P1, acc);
+  }
 }
 
 // L2L: child level lc from parents (table level lc), accumulated.
@@ -365,7 +475,6 @@ __global__ __launch_bounds__(FB) void l2p_p2p_kernel(int p, double kappa, int us
   double2* sxy = reinterpret_cast<double2*>(sh);            // [FB]
   double2* sq = sxy + FB;                                   // [FB] (FP64 strengths)
   float2* sq32 = reinterpret_cast<float2*>(sq + FB);        // [FB] (FP32 strengths)
-  double* I = reinterpret_cast<double*>(sq32 + FB);         // [(p + 1) * FB]
   const int tid = threadIdx.x;
   const int b = blockIdx.x;
   const int s0 = ls[b], cnt = lc[b];
@@ -402,14 +511,16 @@ __global__ __launch_bounds__(FB) void l2p_p2p_kernel(int p, double kappa, int us
     if (use_local && act) {
       const double dx = xi - cx, dy = yi - cy;
       const double rho = sqrt(dx * dx + dy * dy);
-      iseries(kappa * rho, p, I + tid, FB);
+      const double x = kappa * rho, t = 0.25 * x * x, hx = 0.5 * x;
       const double2 e1 = rho > 0.0 ? make_double2(dx / rho, dy / rho) : make_double2(1.0, 0.0);
       const double2* lb = L + (int64_t)b * (p + 1);
-      loc = lb[0].x * I[tid];
+      loc = lb[0].x * iorder(t, 1.0, 0);
       double2 E = e1;
+      double pref = 1.0;                      // (x/2)^n / n!
       for (int n = 1; n <= p; ++n) {
+        pref *= hx * rcp64(double(n));
         const double2 v = cmul(lb[n], E);
-        loc += 2.0 * v.x * I[n * FB + tid];
+        loc += 2.0 * v.x * iorder(t, pref, n);
         E = cmul(E, e1);
       }
     }
@@ -422,31 +533,71 @@ __global__ __launch_bounds__(FB) void l2p_p2p_kernel(int p, double kappa, int us
 
 // ---- host --------------------------------------------------------------------------------
 
+// Bit interleaving for Morton keys (x in the even bits), grid coordinates < 2^31.
+static inline uint64_t spread_bits(uint64_t v) {
+  v &= 0x7fffffffULL;
+  v = (v | (v << 16)) & 0x0000ffff0000ffffULL;
+  v = (v | (v << 8)) & 0x00ff00ff00ff00ffULL;
+  v = (v | (v << 4)) & 0x0f0f0f0f0f0f0f0fULL;
+  v = (v | (v << 2)) & 0x3333333333333333ULL;
+  v = (v | (v << 1)) & 0x5555555555555555ULL;
+  return v;
+}
+static inline uint64_t gather_bits(uint64_t v) {
+  v &= 0x5555555555555555ULL;
+  v = (v | (v >> 1)) & 0x3333333333333333ULL;
+  v = (v | (v >> 2)) & 0x0f0f0f0f0f0f0f0fULL;
+  v = (v | (v >> 4)) & 0x00ff00ff00ff00ffULL;
+  v = (v | (v >> 8)) & 0x0000ffff0000ffffULL;
+  v = (v | (v >> 16)) & 0x00000000ffffffffULL;
+  return v;
+}
 static inline int64_t morton(int64_t ix, int64_t iy) {
-  int64_t k = 0;
-  for (int b = 0; b < 31; ++b) {
-    k |= ((ix >> b) & 1LL) << (2 * b);
-    k |= ((iy >> b) & 1LL) << (2 * b + 1);
-  }
-  return k;
+  return (int64_t)(spread_bits((uint64_t)ix) | (spread_bits((uint64_t)iy) << 1));
 }
 static inline void unmorton(int64_t k, int64_t& ix, int64_t& iy) {
-  ix = iy = 0;
-  for (int b = 0; b < 31; ++b) {
-    ix |= ((k >> (2 * b)) & 1LL) << b;
-    iy |= ((k >> (2 * b + 1)) & 1LL) << b;
+  ix = (int64_t)gather_bits((uint64_t)k);
+  iy = (int64_t)gather_bits((uint64_t)k >> 1);
+}
+
+// Stable LSD radix sort of n (key, index) pairs packed as key << 32 | index,
+// keys below 2^kbits.
+static void radix_sort_keys(std::vector<uint64_t>& a, int kbits) {
+  std::vector<uint64_t> b(a.size());
+  constexpr int D = 11;
+  for (int sh = 32; sh < 32 + kbits; sh += D) {
+    std::vector<size_t> cnt((1 << D) + 1, 0);
+    for (uint64_t v : a) ++cnt[((v >> sh) & ((1 << D) - 1)) + 1];
+    for (int d = 0; d < (1 << D); ++d) cnt[d + 1] += cnt[d];
+    for (uint64_t v : a) b[cnt[(v >> sh) & ((1 << D) - 1)]++] = v;
+    a.swap(b);
   }
 }
 
-template <class T>
-static void up(DevBuf<T>& d, const std::vector<T>& h, hipStream_t s) {
-  d.alloc(std::max<size_t>(h.size(), 1));
-  if (!h.empty()) {
-    // the host vector is usually a temporary: wait for the copy
-    YQ_HIP(hipMemcpyAsync(d.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
-    YQ_HIP(hipStreamSynchronize(s));
+// Host-to-device uploads during set-up: asynchronous, each from a copy held
+// until finish() (or destruction) waits for the stream.
+struct Uploader {
+  hipStream_t s;
+  std::vector<std::shared_ptr<void>> keep;
+  explicit Uploader(hipStream_t st) : s(st) {}
+  Uploader(const Uploader&) = delete;
+  Uploader& operator=(const Uploader&) = delete;
+  ~Uploader() {
+    if (!keep.empty()) (void)hipStreamSynchronize(s);
   }
-}
+  template <class T>
+  void operator()(DevBuf<T>& d, const std::vector<T>& h) {
+    d.alloc(std::max<size_t>(h.size(), 1));
+    if (h.empty()) return;
+    auto c = std::make_shared<std::vector<T>>(h);
+    YQ_HIP(hipMemcpyAsync(d.p, c->data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    keep.push_back(std::move(c));
+  }
+  void finish() {
+    YQ_HIP(hipStreamSynchronize(s));
+    keep.clear();
+  }
+};
 
 // Lookup of occupied boxes by grid position at one level: a dense table while the
 // level's grid is small, a hash map above that.
@@ -482,6 +633,7 @@ void Fmm::build(const double* dx, const double* dy, const double* dwnx, const do
   leaf_max = lmax;
   kappa = kap;
   N = n;
+  Uploader up(s);
   std::vector<double> hx(n), hy(n), hwx(n), hwy(n);
   YQ_HIP(hipMemcpyAsync(hx.data(), dx, n * sizeof(double), hipMemcpyDeviceToHost, s));
   YQ_HIP(hipMemcpyAsync(hy.data(), dy, n * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -500,8 +652,9 @@ void Fmm::build(const double* dx, const double* dy, const double* dwnx, const do
   y0 = 0.5 * (ymin + ymax) - 0.5 * W;
   // Morton keys at the finest candidate depth, sorted once; a coarser level's key
   // is a right shift, so its occupancy is a linear scan of the sorted keys.
-  constexpr int DMAX = 14;
+  YQ_REQUIRE(n < (int64_t)1 << 31, YQ_EINVAL, "FMM: too many nodes");
   std::vector<int64_t> kmax(n);
+  std::vector<uint64_t> packed(n);
   {
     const int64_t m = 1LL << DMAX;
     for (int64_t i = 0; i < n; ++i) {
@@ -509,12 +662,12 @@ void Fmm::build(const double* dx, const double* dy, const double* dwnx, const do
       ix = std::min(std::max(ix, (int64_t)0), m - 1);
       iy = std::min(std::max(iy, (int64_t)0), m - 1);
       kmax[i] = morton(ix, iy);
+      packed[i] = ((uint64_t)kmax[i] << 32) | (uint64_t)i;
     }
   }
+  radix_sort_keys(packed, 2 * DMAX);
   std::vector<int> order_idx(n);
-  std::iota(order_idx.begin(), order_idx.end(), 0);
-  std::stable_sort(order_idx.begin(), order_idx.end(),
-                   [&](int a, int b) { return kmax[a] < kmax[b]; });
+  for (int64_t k = 0; k < n; ++k) order_idx[k] = (int)(packed[k] & 0xffffffffULL);
   depth = DMAX;
   for (int d = 2; d <= DMAX; ++d) {
     const int sh = 2 * (DMAX - d);
@@ -612,25 +765,25 @@ void Fmm::build(const double* dx, const double* dy, const double* dwnx, const do
         hnbp.push_back((int)hnbi.size());
       }
     }
-    up(L.cx, hcx, s);
-    up(L.cy, hcy, s);
-    up(L.parent, hpar, s);
-    up(L.cpos, hpos, s);
-    up(L.ch, hch, s);
+    up(L.cx, hcx);
+    up(L.cy, hcy);
+    up(L.parent, hpar);
+    up(L.cpos, hpos);
+    up(L.ch, hch);
     if (l >= 2) {
-      up(L.ilp, ilp, s);
-      up(L.ils, ils, s);
-      up(L.ilo, ilo, s);
+      up(L.ilp, ilp);
+      up(L.ils, ils);
+      up(L.ilo, ilo);
       std::vector<int> dense((size_t)L.nbox * 49, -1);
       for (int b = 0; b < L.nbox; ++b)
         for (int e = ilp[b]; e < ilp[b + 1]; ++e) dense[(size_t)b * 49 + ilo[e]] = ils[e];
-      up(L.ild, dense, s);
+      up(L.ild, dense);
     }
   }
-  up(leaf_start, hls, s);
-  up(leaf_cnt, hlc, s);
-  up(nbp, hnbp, s);
-  up(nbi, hnbi, s);
+  up(leaf_start, hls);
+  up(leaf_cnt, hlc);
+  up(nbp, hnbp);
+  up(nbi, hnbi);
   std::vector<double> sx(n), sy(n), swx(n), swy(n);
   for (int64_t k = 0; k < n; ++k) {
     const int i = order_idx[k];
@@ -639,13 +792,14 @@ void Fmm::build(const double* dx, const double* dy, const double* dwnx, const do
     swx[k] = hwx[i];
     swy[k] = hwy[i];
   }
-  up(perm, order_idx, s);
-  up(xs, sx, s);
-  up(ys, sy, s);
-  up(wnxs, swx, s);
-  up(wnys, swy, s);
+  up(perm, order_idx);
+  up(xs, sx);
+  up(ys, sy);
+  up(wnxs, swx);
+  up(wnys, swy);
   qx.alloc(n);
   qy.alloc(n);
+  up.finish();
   set_order(order, tab, s);
 }
 
@@ -665,10 +819,23 @@ void Fmm::set_order(int q, const double* tab, hipStream_t s) {
   YQ_HIP(hipGetLastError());
   R16 = ((2 * (p + 1) + 15) / 16) * 16;
   if (use_mfma) {
-    const int64_t rows = (int64_t)(depth + 1) * 49 * R16;
-    amat.alloc((size_t)rows * R16);
-    m2l_amat_kernel<<<(unsigned)((rows + 127) / 128), 128, 0, s>>>(depth, p, R16, ts.p, amat.p);
+    const int64_t vals = (int64_t)(depth + 1) * 49 * R16 * R16;
+    amat.alloc((size_t)vals);
+    trans_amat_kernel<<<(unsigned)((vals + 255) / 256), 256, 0, s>>>(depth + 1, 49, p, R16, 1, ts.p,
+                                                                       amat.p);
+    const int64_t gvals = (int64_t)(depth + 1) * 4 * R16 * R16;
+    gmat.alloc((size_t)gvals);
+    trans_amat_kernel<<<(unsigned)((gvals + 255) / 256), 256, 0, s>>>(depth + 1, 4, p, R16, 0, tg.p,
+                                                                        gmat.p);
     YQ_HIP(hipGetLastError());
+    // 16-box tiles of every level with M2L terms, finest level first
+    Uploader up(s);
+    std::vector<int2> ht;
+    for (int l = depth; l >= 2; --l)
+      for (int b = 0; b < lv[l].nbox; b += 16) ht.push_back(make_int2(l, b));
+    up(m2l_tiles, ht);
+    up.finish();
+    n_m2l_tiles = (int)ht.size();
   }
   YQ_HIP(hipStreamSynchronize(s));
   built = true;
@@ -721,6 +888,59 @@ void Fmm::copy_tree(const Fmm& o, int q, const double* tab, hipStream_t s) {
   set_order(q, tab, s);
 }
 
+void Fmm::m2l_mfma(hipStream_t s) {
+  M2LLevels a{};
+  for (int l = 2; l <= depth; ++l) {
+    a.ild[l] = lv[l].ild.p;
+    a.M[l] = lv[l].M.p;
+    a.L[l] = lv[l].L.p;
+    a.nbox[l] = lv[l].nbox;
+  }
+  const int RT = R16 / 16;
+  const unsigned g = (unsigned)(n_m2l_tiles * RT);   // one block per (tile, row tile)
+  if (g == 0) return;
+  const int64_t ls = (int64_t)49 * R16 * R16;
+  switch (RT) {
+    case 1: m2l_mfma_kernel<1><<<g, 256, 0, s>>>(p, m2l_tiles.p, a, amat.p, ls); break;
+    case 2: m2l_mfma_kernel<2><<<g, 256, 0, s>>>(p, m2l_tiles.p, a, amat.p, ls); break;
+    case 3: m2l_mfma_kernel<3><<<g, 256, 0, s>>>(p, m2l_tiles.p, a, amat.p, ls); break;
+    case 4: m2l_mfma_kernel<4><<<g, 256, 0, s>>>(p, m2l_tiles.p, a, amat.p, ls); break;
+    case 5: m2l_mfma_kernel<5><<<g, 256, 0, s>>>(p, m2l_tiles.p, a, amat.p, ls); break;
+    case 6: m2l_mfma_kernel<6><<<g, 256, 0, s>>>(p, m2l_tiles.p, a, amat.p, ls); break;
+    default: m2l_mfma_kernel<7><<<g, 256, 0, s>>>(p, m2l_tiles.p, a, amat.p, ls); break;
+  }
+  YQ_HIP(hipGetLastError());
+}
+
+// M2M into parent level l (gather) or L2L from parent level l (scatter), both
+// with the child level's position matrices.
+void Fmm::tree_mfma(bool gather, int l, hipStream_t s) {
+  const int nb = lv[l].nbox;
+  if (nb == 0) return;
+  const int RT = R16 / 16;
+  const unsigned g = (unsigned)(((nb + 15) / 16) * RT);   // one block per (tile, row tile)
+  const double* A = gmat.p + (size_t)(l + 1) * 4 * R16 * R16;
+  const double2* X = gather ? lv[l + 1].M.p : lv[l].L.p;
+  double2* Y = gather ? lv[l].M.p : lv[l + 1].L.p;
+  const int* ch = lv[l].ch.p;
+#define YQ_TREE(rt)                                                                  \
+  if (gather)                                                                        \
+    tree_mfma_kernel<rt, true><<<g, 256, 0, s>>>(p, nb, ch, X, A, Y);                 \
+  else                                                                               \
+    tree_mfma_kernel<rt, false><<<g, 256, 0, s>>>(p, nb, ch, X, A, Y);
+  switch (RT) {
+    case 1: YQ_TREE(1) break;
+    case 2: YQ_TREE(2) break;
+    case 3: YQ_TREE(3) break;
+    case 4: YQ_TREE(4) break;
+    case 5: YQ_TREE(5) break;
+    case 6: YQ_TREE(6) break;
+    default: YQ_TREE(7) break;
+  }
+#undef YQ_TREE
+  YQ_HIP(hipGetLastError());
+}
+
 void Fmm::apply(const double* sigma, double* partial, bool p2p_fp32, const double* tab,
                 hipStream_t s) {
   YQ_REQUIRE(built, YQ_ESTATE, "FMM tree not built");
@@ -728,46 +948,40 @@ void Fmm::apply(const double* sigma, double* partial, bool p2p_fp32, const doubl
   gather_kernel<<<(unsigned)((N + 255) / 256), 256, 0, s>>>(N, perm.p, sigma, wnxs.p, wnys.p, qx.p,
                                                             qy.p);
   FmmLevel& leaf = lv[depth];
-  const int pb = (3 * p + 4) * FB * sizeof(double) <= 48 * 1024 ? FB : FB / 2;
-  const size_t sh_p2m = (size_t)(3 * p + 4) * pb * sizeof(double);
-  p2m_kernel<<<leaf.nbox, pb, sh_p2m, s>>>(p, kappa, leaf_start.p, leaf_cnt.p, leaf.cx.p, leaf.cy.p,
-                                           xs.p, ys.p, qx.p, qy.p, leaf.M.p);
+  p2m_kernel<<<leaf.nbox, 64, 0, s>>>(p, kappa, leaf_start.p, leaf_cnt.p, leaf.cx.p, leaf.cy.p, xs.p,
+                                      ys.p, qx.p, qy.p, leaf.M.p);
   for (int l = depth - 1; l >= 2; --l) {
+    if (use_mfma) {
+      tree_mfma(true, l, s);
+      continue;
+    }
     const int64_t nt = (int64_t)lv[l].nbox * (p + 1);
     m2m_kernel<<<(unsigned)((nt + 127) / 128), 128, 0, s>>>(p, lv[l].nbox, lv[l].ch.p, lv[l + 1].M.p,
                                                             tg.p + (size_t)(l + 1) * 4 * K,
                                                             lv[l].M.p);
   }
-  for (int l = 2; l <= depth; ++l) {
-    const int nb = lv[l].nbox;
-    if (use_mfma) {
-      const double* A = amat.p + (size_t)l * 49 * R16 * R16;
-      const unsigned g = (unsigned)((nb + 63) / 64);
-      switch (R16 / 16) {
-        case 1: m2l_mfma_kernel<1><<<g, 256, 0, s>>>(p, nb, lv[l].ild.p, lv[l].M.p, A, lv[l].L.p); break;
-        case 2: m2l_mfma_kernel<2><<<g, 256, 0, s>>>(p, nb, lv[l].ild.p, lv[l].M.p, A, lv[l].L.p); break;
-        case 3: m2l_mfma_kernel<3><<<g, 256, 0, s>>>(p, nb, lv[l].ild.p, lv[l].M.p, A, lv[l].L.p); break;
-        case 4: m2l_mfma_kernel<4><<<g, 256, 0, s>>>(p, nb, lv[l].ild.p, lv[l].M.p, A, lv[l].L.p); break;
-        case 5: m2l_mfma_kernel<5><<<g, 256, 0, s>>>(p, nb, lv[l].ild.p, lv[l].M.p, A, lv[l].L.p); break;
-        case 6: m2l_mfma_kernel<6><<<g, 256, 0, s>>>(p, nb, lv[l].ild.p, lv[l].M.p, A, lv[l].L.p); break;
-        default: m2l_mfma_kernel<7><<<g, 256, 0, s>>>(p, nb, lv[l].ild.p, lv[l].M.p, A, lv[l].L.p); break;
-      }
-    } else {
-      const int64_t nt = (int64_t)nb * (p + 1);
-      m2l_kernel<<<(unsigned)((nt + 127) / 128), 128, 0, s>>>(p, nb, lv[l].ilp.p, lv[l].ils.p,
+  if (use_mfma) {
+    m2l_mfma(s);
+  } else {
+    for (int l = 2; l <= depth; ++l) {
+      const int64_t nt = (int64_t)lv[l].nbox * (p + 1);
+      m2l_kernel<<<(unsigned)((nt + 127) / 128), 128, 0, s>>>(p, lv[l].nbox, lv[l].ilp.p, lv[l].ils.p,
                                                               lv[l].ilo.p, lv[l].M.p,
                                                               ts.p + (size_t)l * 49 * K, lv[l].L.p);
     }
   }
   for (int l = 2; l < depth; ++l) {
+    if (use_mfma) {
+      tree_mfma(false, l, s);
+      continue;
+    }
     const int64_t nt = (int64_t)lv[l + 1].nbox * (p + 1);
     l2l_kernel<<<(unsigned)((nt + 127) / 128), 128, 0, s>>>(p, lv[l + 1].nbox, lv[l + 1].parent.p,
                                                             lv[l + 1].cpos.p, lv[l].L.p,
                                                             tg.p + (size_t)(l + 1) * 4 * K,
                                                             lv[l + 1].L.p);
   }
-  const size_t sh_l = (size_t)FB * (2 * sizeof(double2) + sizeof(float2)) +
-                      (size_t)(p + 1) * FB * sizeof(double);
+  const size_t sh_l = (size_t)FB * (2 * sizeof(double2) + sizeof(float2));
   if (p2p_fp32)
     l2p_p2p_kernel<true><<<leaf.nbox, FB, sh_l, s>>>(p, kappa, 1, leaf_start.p, leaf_cnt.p, nbp.p,
                                                      nbi.p, leaf.cx.p, leaf.cy.p, leaf.L.p, xs.p, ys.p,
