@@ -171,7 +171,10 @@ int yq_apply_operator(yq_problem* prob, const double* sigma, double* out, int32_
 int yq_solve(yq_problem* prob, const double* sigma0, double* sigma, yq_solve_info* info);
 
 /* Exterior-limit surface gradient of u = D[sigma] at the nodes (step a10):
- * dev gx, gy [N].  Asynchronous. */
+ * dev gx, gy [N].  The far part is the direct FP64 sum, or with the FMM
+ * enabled the FP64 FMM gradient (order fmm_resid_order, else fmm_order): the
+ * local expansions' gradient plus direct neighbour-leaf interactions.
+ * Asynchronous. */
 int yq_surface_gradient(yq_problem* prob, const double* sigma, double* gx, double* gy);
 
 /* Hydrophobic forces and torques (step a11, eqs. stress, force_torque,

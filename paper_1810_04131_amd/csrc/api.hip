@@ -714,17 +714,34 @@ int yq_solve(yq_problem* pb, const double* sigma0, double* sigma, yq_solve_info*
   return status;
 }
 
+namespace {
+
+// Gradient far field of sigma into pb->gpartial: the FMM (its FP64 residual
+// instance when there is one) when the FMM is enabled, else the direct sum.
+// Returns the chunk plan the finishing kernel reads it with.
+FarPlan far_grad(yq_problem* pb, const double* sigma) {
+  Timed t(pb, 3);
+  Fmm* fmm = pb->fmm_hi ? pb->fmm_hi.get() : pb->fmm.get();
+  if (fmm) {
+    pb->gpartial.reserve((size_t)2 * pb->N);
+    fmm->apply_grad(sigma, pb->gpartial.p, pb->tab.p, pb->stream);
+    FarPlan one = pb->fp;
+    one.chunks = 1;
+    return one;
+  }
+  pb->gpartial.reserve((size_t)pb->fp.chunks * 2 * pb->N);
+  launch_far_grad64(pb->view(), sigma, pb->fp, pb->gpartial.p, pb->stream);
+  return pb->fp;
+}
+
+}  // namespace
+
 int yq_surface_gradient(yq_problem* pb, const double* sigma, double* gx, double* gy) {
   return guarded(pb, [&] {
     require_ready(pb);
     YQ_REQUIRE(sigma && gx && gy, YQ_EINVAL, "null argument");
-    pb->gpartial.reserve((size_t)pb->fp.chunks * 2 * pb->N);
-    GeomView g = pb->view();
-    {
-      Timed t(pb, 3);
-      launch_far_grad64(g, sigma, pb->fp, pb->gpartial.p, pb->stream);
-    }
-    launch_finish_grad(g, pb->prm.qbx_window, pb->fp, pb->gpartial.p, pb->WGx.p, pb->WGy.p,
+    const FarPlan fp = far_grad(pb, sigma);
+    launch_finish_grad(pb->view(), pb->prm.qbx_window, fp, pb->gpartial.p, pb->WGx.p, pb->WGy.p,
                        pb->xrow.p, pb->xpan.p, pb->xgvals.p, sigma, gx, gy, pb->stream);
   });
 }
@@ -735,15 +752,11 @@ int yq_forces(yq_problem* pb, const double* sigma, double gamma, double* force, 
     require_ready(pb);
     YQ_REQUIRE(sigma && force && torque, YQ_EINVAL, "null argument");
     YQ_REQUIRE(pb->have_f, YQ_ESTATE, "boundary data not set");
-    pb->gpartial.reserve((size_t)pb->fp.chunks * 2 * pb->N);
     pb->gx.reserve(pb->N);
     pb->gy.reserve(pb->N);
     GeomView g = pb->view();
-    {
-      Timed t(pb, 3);
-      launch_far_grad64(g, sigma, pb->fp, pb->gpartial.p, pb->stream);
-    }
-    launch_finish_grad(g, pb->prm.qbx_window, pb->fp, pb->gpartial.p, pb->WGx.p, pb->WGy.p,
+    const FarPlan fp = far_grad(pb, sigma);
+    launch_finish_grad(g, pb->prm.qbx_window, fp, pb->gpartial.p, pb->WGx.p, pb->WGy.p,
                        pb->xrow.p, pb->xpan.p, pb->xgvals.p, sigma, pb->gx.p, pb->gy.p, pb->stream);
     launch_forces(g, pb->f.p, pb->gx.p, pb->gy.p, gamma, force, torque, pb->en.p, pb->stream);
     std::vector<double> e(pb->n);

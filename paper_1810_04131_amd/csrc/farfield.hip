@@ -123,20 +123,7 @@ __global__ __launch_bounds__(FAR_BS) void far_grad64_kernel(GeomView g,
     }
     __syncthreads();
     const int nb = (int)min((int64_t)FAR_BS, j1 - jb);
-    for (int k = 0; k < nb; ++k) {
-      const double2 p = sxy[k];
-      const double2 q = sq[k];
-      const double dx = xi - p.x, dy = yi - p.y;
-      const double r2 = fma(dx, dx, dy * dy);
-      if (r2 > 0.0) {
-        double k0, k1z;
-        k0_k1z_64(kap2 * r2, k0, k1z, g.tab);
-        const double dq = fma(dx, q.x, dy * q.y);
-        const double b = dq * (k0 + 2.0 * k1z) * rcp64(r2);
-        ax += k1z * q.x - b * dx;
-        ay += k1z * q.y - b * dy;
-      }
-    }
+    far_grad64_tile(xi, yi, sxy, sq, nb, kap2, g.tab, ax, ay);
   }
   if (i < N) {
     partial[((int64_t)blockIdx.y * 2 + 0) * N + i] = ax;

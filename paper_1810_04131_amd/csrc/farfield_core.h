@@ -36,6 +36,29 @@ __device__ __forceinline__ float far32_tile(double xi, double yi, const double2*
   return acc;
 }
 
+// Gradient of the double layer over a staged source tile, accumulated into
+// (ax, ay) in the scaling of far64_tile:
+// (K1(z)/z) q - ((x-y).q) (x-y) (K0(z) + 2 K1(z)/z) / r^2, self pair skipped.
+__device__ __forceinline__ void far_grad64_tile(double xi, double yi, const double2* sxy,
+                                                const double2* sq, int nb, double kap2,
+                                                const double* __restrict__ tab, double& ax,
+                                                double& ay) {
+  for (int k = 0; k < nb; ++k) {
+    const double2 p = sxy[k];
+    const double2 q = sq[k];
+    const double dx = xi - p.x, dy = yi - p.y;
+    const double r2 = fma(dx, dx, dy * dy);
+    if (r2 > 0.0) {
+      double k0, k1z;
+      k0_k1z_64(kap2 * r2, k0, k1z, tab);
+      const double dq = fma(dx, q.x, dy * q.y);
+      const double b = dq * (k0 + 2.0 * k1z) * rcp64(r2);
+      ax += k1z * q.x - b * dx;
+      ay += k1z * q.y - b * dy;
+    }
+  }
+}
+
 // Window + extra-near correction of target i (local index) for density sg.
 __device__ __forceinline__ double correction_row(int64_t i, int64_t N, int P, int win,
                                                  const double* __restrict__ W,

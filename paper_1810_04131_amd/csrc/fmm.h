@@ -49,6 +49,9 @@ struct Fmm {
   // partial[i] = (2 pi / kappa^2) * far field at node i (the far-field kernels' scaling)
   void m2l_mfma(hipStream_t s);
   void tree_mfma(bool gather, int l, hipStream_t s);
+  void expansions(const double* sigma, hipStream_t s);
+  // gpart[i], gpart[N + i] = (2 pi / kappa^2) * gradient of the far field at node i (FP64)
+  void apply_grad(const double* sigma, double* gpart, const double* tab, hipStream_t s);
   void apply(const double* sigma, double* partial, bool p2p_fp32, const double* tab,
              hipStream_t s);
 };

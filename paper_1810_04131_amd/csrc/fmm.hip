@@ -531,6 +531,87 @@ __global__ __launch_bounds__(FB) void l2p_p2p_kernel(int p, double kappa, int us
   }
 }
 
+// Gradient counterpart of l2p_p2p_kernel (FP64): the direct gradient from the
+// 3 x 3 neighbourhood plus the local expansion's gradient
+//   u_x + i u_y = kappa [ L_0 I_1 e^{i theta}
+//                 + sum_{n>=1} (L_n I_{n+1} e^{i(n+1) theta} + conj(L_n) I_{n-1} e^{-i(n-1) theta}) ],
+// since (d/dx + i d/dy) I_n(kappa rho) e^{i n theta} = kappa I_{n+1} e^{i(n+1) theta} for
+// every integer n (I_{-n} = I_n).  Writes gpart[node] (x) and gpart[N + node] (y) in
+// the gradient far-field kernels' scaling.
+__global__ __launch_bounds__(FB) void l2p_p2p_grad_kernel(int p, double kappa,
+                                                          const int* __restrict__ ls,
+                                                          const int* __restrict__ lc,
+                                                          const int* __restrict__ nbp,
+                                                          const int* __restrict__ nbi,
+                                                          const double* __restrict__ ccx,
+                                                          const double* __restrict__ ccy,
+                                                          const double2* __restrict__ L,
+                                                          const double* __restrict__ xs,
+                                                          const double* __restrict__ ys,
+                                                          const double* __restrict__ qx,
+                                                          const double* __restrict__ qy,
+                                                          const int* __restrict__ perm, int64_t N,
+                                                          const double* __restrict__ tab,
+                                                          double* __restrict__ gpart) {
+  extern __shared__ double sh[];
+  double2* sxy = reinterpret_cast<double2*>(sh);            // [FB]
+  double2* sq = sxy + FB;                                   // [FB]
+  const int tid = threadIdx.x;
+  const int b = blockIdx.x;
+  const int s0 = ls[b], cnt = lc[b];
+  const double kap2 = kappa * kappa;
+  const double cx = ccx[b], cy = ccy[b];
+  for (int r0 = 0; r0 < cnt; r0 += FB) {
+    const int j = r0 + tid;
+    const bool act = j < cnt;
+    const double xi = act ? xs[s0 + j] : cx, yi = act ? ys[s0 + j] : cy;
+    double ax = 0.0, ay = 0.0;
+    for (int e = nbp[b]; e < nbp[b + 1]; ++e) {
+      const int nb = nbi[e];
+      const int t0 = ls[nb], tc = lc[nb];
+      for (int k0 = 0; k0 < tc; k0 += FB) {
+        __syncthreads();
+        if (k0 + tid < tc) {
+          const int k = t0 + k0 + tid;
+          sxy[tid] = make_double2(xs[k], ys[k]);
+          sq[tid] = make_double2(qx[k], qy[k]);
+        }
+        __syncthreads();
+        far_grad64_tile(xi, yi, sxy, sq, min(FB, tc - k0), kap2, tab, ax, ay);
+      }
+    }
+    if (act) {
+      const double dx = xi - cx, dy = yi - cy;
+      const double rho = sqrt(dx * dx + dy * dy);
+      const double x = kappa * rho, t = 0.25 * x * x, hx = 0.5 * x;
+      const double2 e1 = rho > 0.0 ? make_double2(dx / rho, dy / rho) : make_double2(1.0, 0.0);
+      const double2* lb = L + (int64_t)b * (p + 1);
+      double pref = hx;                                   // (x/2)^{n+1} / (n+1)!
+      double Iprev = iorder(t, 1.0, 0);                   // I_{n-1}
+      double Icur = iorder(t, pref, 1);                   // I_n
+      double2 G = make_double2(lb[0].x * Icur * e1.x, lb[0].x * Icur * e1.y);
+      double2 Eprev = make_double2(1.0, 0.0);             // e^{i(n-1) theta}
+      double2 Enext = e1;                                 // e^{i(n+1) theta} after the update
+      for (int n = 1; n <= p; ++n) {
+        pref *= hx * rcp64(double(n + 1));
+        const double Inext = iorder(t, pref, n + 1);
+        Enext = cmul(Enext, e1);
+        const double2 a = cmul(lb[n], Enext);
+        const double2 c = cconj(cmul(lb[n], Eprev));
+        G.x += a.x * Inext + c.x * Iprev;
+        G.y += a.y * Inext + c.y * Iprev;
+        Eprev = cmul(Eprev, e1);
+        Iprev = Icur;
+        Icur = Inext;
+      }
+      const double sc = kappa * 2.0 * PI / kap2;
+      const int node = perm[s0 + j];
+      gpart[node] = ax + G.x * sc;
+      gpart[N + node] = ay + G.y * sc;
+    }
+  }
+}
+
 // ---- host --------------------------------------------------------------------------------
 
 // Bit interleaving for Morton keys (x in the even bits), grid coordinates < 2^31.
@@ -941,8 +1022,9 @@ void Fmm::tree_mfma(bool gather, int l, hipStream_t s) {
   YQ_HIP(hipGetLastError());
 }
 
-void Fmm::apply(const double* sigma, double* partial, bool p2p_fp32, const double* tab,
-                hipStream_t s) {
+// Multipole and local expansions of the leaves for density sigma (upward pass,
+// M2L, downward pass).
+void Fmm::expansions(const double* sigma, hipStream_t s) {
   YQ_REQUIRE(built, YQ_ESTATE, "FMM tree not built");
   const int K = 4 * p + 1;
   gather_kernel<<<(unsigned)((N + 255) / 256), 256, 0, s>>>(N, perm.p, sigma, wnxs.p, wnys.p, qx.p,
@@ -981,6 +1063,12 @@ void Fmm::apply(const double* sigma, double* partial, bool p2p_fp32, const doubl
                                                             tg.p + (size_t)(l + 1) * 4 * K,
                                                             lv[l + 1].L.p);
   }
+}
+
+void Fmm::apply(const double* sigma, double* partial, bool p2p_fp32, const double* tab,
+                hipStream_t s) {
+  expansions(sigma, s);
+  FmmLevel& leaf = lv[depth];
   const size_t sh_l = (size_t)FB * (2 * sizeof(double2) + sizeof(float2));
   if (p2p_fp32)
     l2p_p2p_kernel<true><<<leaf.nbox, FB, sh_l, s>>>(p, kappa, 1, leaf_start.p, leaf_cnt.p, nbp.p,
@@ -990,6 +1078,16 @@ void Fmm::apply(const double* sigma, double* partial, bool p2p_fp32, const doubl
     l2p_p2p_kernel<false><<<leaf.nbox, FB, sh_l, s>>>(p, kappa, 1, leaf_start.p, leaf_cnt.p, nbp.p,
                                                       nbi.p, leaf.cx.p, leaf.cy.p, leaf.L.p, xs.p,
                                                       ys.p, qx.p, qy.p, perm.p, tab, partial);
+  YQ_HIP(hipGetLastError());
+}
+
+void Fmm::apply_grad(const double* sigma, double* gpart, const double* tab, hipStream_t s) {
+  expansions(sigma, s);
+  FmmLevel& leaf = lv[depth];
+  const size_t sh = (size_t)FB * 2 * sizeof(double2);
+  l2p_p2p_grad_kernel<<<leaf.nbox, FB, sh, s>>>(p, kappa, leaf_start.p, leaf_cnt.p, nbp.p, nbi.p,
+                                                 leaf.cx.p, leaf.cy.p, leaf.L.p, xs.p, ys.p, qx.p,
+                                                 qy.p, perm.p, N, tab, gpart);
   YQ_HIP(hipGetLastError());
 }
 

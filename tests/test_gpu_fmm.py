@@ -64,6 +64,29 @@ def test_fmm_m2l_matrix_cores_match_vector_alu(medium, order):
     assert _rel(out[yq.YQ_M2L_MFMA], out[yq.YQ_M2L_VALU]) < 1e-12
 
 
+def test_fmm_gradient_and_forces_match_direct(medium):
+    # surface gradient and forces with the FP64 FMM far part (order 40) against
+    # the direct FP64 sum on the same density
+    torch = _torch()
+    parts = medium["particles"]
+    out = {}
+    for mode in (yq.YQ_FAR_DIRECT, yq.YQ_FAR_FMM):
+        pb = yq.Problem(yq.default_params(far_mode=mode, fmm_order=20, fmm_resid_order=40))
+        pb.set_workload(parts)
+        f = pb.boundary_label()
+        pb.set_boundary_data(f)
+        sig = torch.tensor(workloads.random_density(pb.N, 8), device="cuda", dtype=torch.float64)
+        gx, gy = pb.surface_gradient(sig)
+        F, T, E = pb.forces(sig)
+        out[mode] = (_np(gx), _np(gy), _np(F), _np(T), E)
+    d, m = out[yq.YQ_FAR_DIRECT], out[yq.YQ_FAR_FMM]
+    g_ref = np.hypot(d[0], d[1]).max()
+    assert np.abs(m[0] - d[0]).max() < 1e-9 * g_ref and np.abs(m[1] - d[1]).max() < 1e-9 * g_ref
+    sc = max(np.abs(d[2]).max(), np.abs(d[3]).max())
+    assert np.abs(m[2] - d[2]).max() < 1e-9 * sc and np.abs(m[3] - d[3]).max() < 1e-9 * sc
+    assert abs(m[4] - d[4]) < 1e-9 * abs(d[4])
+
+
 def test_fmm_far_field_against_oracle_rows(medium):
     _torch()
     parts = medium["particles"]
