@@ -256,14 +256,26 @@ int yq_batch_use_graphs(yq_batch* batch, int32_t enable);
  *   resources released).
  * Work of requests in flight shares every fused launch; a request's arithmetic
  * depends only on its own size, so its result is the same alone or in a mix.
- * Latency = completion time - submit time (steady clock).  The server owns a
- * HIP stream of default priority; calls are synchronous. */
+ * FMM lane: requests of at least a threshold node count (params->far_mode
+ * YQ_FAR_FMM: every request; YQ_FAR_AUTO: 60000 nodes; YQ_FAR_DIRECT: none;
+ * yq_server_set_fmm overrides) are admitted by the memory budget alone (not the
+ * arena) and solved each as a standalone problem with the FMM far field
+ * (section 5's fast multipole evaluation; mixed precision with FP64 FMM
+ * residuals and forces) by worker threads, each with its own stream of
+ * default priority, concurrently with the fused iterations; results likewise
+ * depend only on the request.  Latency = completion time - submit time
+ * (steady clock).  The server owns a HIP stream of default priority; calls
+ * other than the lane's solves are synchronous. */
 typedef struct yq_server yq_server;
 
 int yq_server_create(const yq_params* params, int64_t node_capacity, int32_t max_slots,
                      double mem_budget_bytes, yq_server** out);
 void yq_server_destroy(yq_server* server);
 const char* yq_server_last_error(const yq_server* server);
+
+/* FMM lane threshold (nodes, >= 0) and worker count (1..8); only before the
+ * first submit (YQ_ESTATE after). */
+int yq_server_set_fmm(yq_server* server, int64_t min_nodes, int32_t workers);
 
 /* Queues a request (host arrays copied; label as yq_boundary_label).  ticket:
  * host out.  YQ_EADMIT (ticket still set, state failed) if the request can
@@ -285,7 +297,8 @@ int yq_server_result(yq_server* server, int64_t ticket, int32_t* state, int64_t*
 /* Forgets a finished request's stored results. */
 int yq_server_release(yq_server* server, int64_t ticket);
 
-/* Removes a queued or running request (it ends in state failed, "cancelled"). */
+/* Removes a queued or running request (it ends in state failed, "cancelled"; a
+ * running FMM-lane request when its solve returns, at a later yq_server_step). */
 int yq_server_cancel(yq_server* server, int64_t ticket);
 
 /* Per-phase GPU timers: with profiling enabled every launch of a phase is

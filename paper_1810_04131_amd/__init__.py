@@ -317,6 +317,11 @@ class Server:
         except Exception:
             pass
 
+    def set_fmm(self, min_nodes, workers=2):
+        """Requests of at least min_nodes nodes take the FMM lane (before the first submit)."""
+        self._check(self.lib.yq_server_set_fmm(self.h, int(min_nodes), int(workers)))
+        return self
+
     def submit(self, particles, label_kind=YQ_LABEL_ARC, a=0.7853981633974483, b=0.1):
         import numpy as np
         c = np.ascontiguousarray(np.asarray(particles.center, float).reshape(-1))

@@ -109,6 +109,7 @@ SIGNATURES = {
                                    ctypes.POINTER(c_void_p)]),
     "yq_server_destroy": (None, [P]),
     "yq_server_last_error": (c_char_p, [P]),
+    "yq_server_set_fmm": (c_int32, [P, c_int64, c_int32]),
     "yq_server_submit": (c_int32, [P, c_int32, P, P, P, c_double, c_int32, c_double, c_double,
                                    ctypes.POINTER(c_int64)]),
     "yq_server_step": (c_int32, [P, ctypes.POINTER(c_int32), ctypes.POINTER(c_int32),

@@ -14,9 +14,6 @@ using namespace yq;
 
 namespace {
 
-// YQ_FAR_AUTO switches the inner operator to the FMM from this many nodes on.
-constexpr int64_t kFmmAutoNodes = 60000;
-
 thread_local std::string g_last_error;
 
 // Brackets the launches issued in its scope with a pair of events when profiling is on.

@@ -19,13 +19,25 @@
 // Requests therefore join and leave the running set between iterations, their
 // work shares every fused launch, and each request's arithmetic is the same as
 // when it runs alone (its plans depend only on its own size).
+//
+// Requests of at least fmm_min_nodes nodes take the FMM lane instead: admitted
+// by the memory budget alone, each is solved as a standalone problem with the
+// FMM far field (mixed precision, FP64 FMM residuals and forces) by one of a
+// few worker threads, each on its own stream, so that their kernels overlap on
+// the device with the fused iterations of the small requests.  A request's
+// result depends only on the request.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
+#include <condition_variable>
 #include <deque>
+#include <limits>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
+#include <thread>
 
 #include "batch.h"
 #include "common.h"
@@ -91,6 +103,8 @@ struct Request {
   int64_t N = 0;
   double est_bytes = 0.0;
   double t_submit = 0.0, t_done = 0.0;
+  bool fmm_lane = false;
+  std::atomic<bool> cancel{false};
   // running state
   int slot = -1;
   int64_t off = 0;
@@ -123,6 +137,18 @@ struct yq_server {
   DevBuf<int> d_slots;
   DevBuf<double> d_vals;
   int64_t completed_total = 0;
+  // FMM lane
+  int device = 0;
+  int64_t fmm_min_nodes = std::numeric_limits<int64_t>::max();
+  int fmm_workers = 2;
+  int fmm_inflight = 0;                 // admitted to the lane and not yet collected
+  std::mutex mu;
+  std::condition_variable cv;           // work for the workers
+  std::condition_variable cv_done;      // a worker finished a request
+  std::deque<Request*> fmm_queue;       // waiting for a worker (guarded by mu)
+  std::vector<Request*> fmm_done;       // finished by a worker (guarded by mu)
+  bool stop = false;                    // guarded by mu
+  std::vector<std::thread> workers;
 };
 
 namespace {
@@ -154,6 +180,109 @@ double estimate_bytes(const yq_params& p, int64_t N) {
   const double per_node = 7 * 8 + 2 * 4 + 3.0 * (2 * p.qbx_window + 1) * Q * 8 + 8 * 6 + 4 * 2;
   const FarPlan fp = far_plan(N, N, 256, 4096);
   return N * per_node + (double)fp.chunks * N * 12 + (double)fp.chunks * 2 * N * 8 + (1 << 20);
+}
+
+// The same for an FMM-lane request: geometry and QBX correction, the Krylov
+// basis and work vectors, the two FMM instances.
+double estimate_fmm_bytes(const yq_params& p, int64_t N) {
+  const double per_node = 7 * 8 + 2 * 4 + 3.0 * (2 * p.qbx_window + 1) * Q * 8 + 8 * 6 + 4 * 2;
+  return N * (per_node + 8.0 * (p.restart + 8) + 160.0) + (128 << 20);
+}
+
+// Solves one FMM-lane request on the calling worker's stream; fills its results.
+void run_fmm_request(const yq_params& prm, Request* r, hipStream_t st) {
+  yq_params p = prm;
+  p.far_mode = YQ_FAR_FMM;
+  yq_problem* raw = nullptr;
+  int status = yq_create(&p, &raw);
+  std::unique_ptr<yq_problem, void (*)(yq_problem*)> pb(raw, yq_destroy);
+  std::string err = status == YQ_OK ? "" : yq_last_error(nullptr);
+  try {
+    if (status == YQ_OK) status = yq_set_stream(pb.get(), st);
+    if (status == YQ_OK)
+      status = yq_set_particles(pb.get(), r->n, r->center.data(), r->angle.data(), r->axes.data(),
+                                r->kappa);
+    DevBuf<double> f, sg, F, Tq;
+    if (status == YQ_OK) {
+      f.alloc(r->N);
+      sg.alloc(r->N);
+      F.alloc(2 * r->n);
+      Tq.alloc(r->n);
+      status = yq_boundary_label(pb.get(), r->label_kind, r->p0, r->p1, f.p);
+    }
+    if (status == YQ_OK) status = yq_set_boundary_data(pb.get(), f.p);
+    int solved = YQ_EDEVICE;
+    if (status == YQ_OK) {
+      solved = yq_solve(pb.get(), nullptr, sg.p, &r->info);
+      status = (solved == YQ_OK || solved == YQ_ENOCONV) ? YQ_OK : solved;
+    }
+    if (status == YQ_OK) status = yq_forces(pb.get(), sg.p, 1.0, F.p, Tq.p, &r->energy);
+    if (status == YQ_OK) {
+      r->sigma.assign(r->N, 0.0);
+      r->force.assign(2 * r->n, 0.0);
+      r->torque.assign(r->n, 0.0);
+      YQ_HIP(hipMemcpyAsync(r->sigma.data(), sg.p, r->N * sizeof(double), hipMemcpyDeviceToHost, st));
+      YQ_HIP(hipMemcpyAsync(r->force.data(), F.p, 2 * r->n * sizeof(double), hipMemcpyDeviceToHost,
+                            st));
+      YQ_HIP(hipMemcpyAsync(r->torque.data(), Tq.p, r->n * sizeof(double), hipMemcpyDeviceToHost,
+                            st));
+      YQ_HIP(hipStreamSynchronize(st));
+      status = solved;      // YQ_OK or YQ_ENOCONV
+    } else if (pb) {
+      err = yq_last_error(pb.get());
+    }
+  } catch (const Error& e) {
+    status = e.code;
+    err = e.msg;
+  } catch (const std::exception& e) {
+    status = YQ_EDEVICE;
+    err = e.what();
+  }
+  r->status = status;
+  r->err = err;
+  r->rel = r->info.residual;
+}
+
+void fmm_worker(yq_server* s) {
+  (void)hipSetDevice(s->device);
+  hipStream_t st = nullptr;
+  const bool have_stream = hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess;
+  for (;;) {
+    Request* r = nullptr;
+    {
+      std::unique_lock<std::mutex> lk(s->mu);
+      s->cv.wait(lk, [&] { return s->stop || !s->fmm_queue.empty(); });
+      if (s->stop) break;
+      r = s->fmm_queue.front();
+      s->fmm_queue.pop_front();
+    }
+    if (r->cancel.load()) {
+      r->status = YQ_ESTATE;
+      r->err = "cancelled";
+    } else if (!have_stream) {
+      r->status = YQ_EDEVICE;
+      r->err = "worker stream creation failed";
+    } else {
+      run_fmm_request(s->prm, r, st);
+    }
+    r->t_done = now_s();
+    {
+      std::lock_guard<std::mutex> lk(s->mu);
+      s->fmm_done.push_back(r);
+    }
+    s->cv_done.notify_all();
+  }
+  if (have_stream) (void)hipStreamDestroy(st);
+}
+
+void stop_workers(yq_server* s) {
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stop = true;
+  }
+  s->cv.notify_all();
+  for (auto& t : s->workers) t.join();
+  s->workers.clear();
 }
 
 bool take_range(yq_server* s, int64_t N, int64_t& off) {
@@ -239,18 +368,35 @@ int yq_server_create(const yq_params* params, int64_t node_capacity, int32_t max
     s->eng.upload_mask(s->eng.inc, std::vector<int>(max_slots, 0));
     s->d_slots.alloc(max_slots);
     s->d_vals.alloc(3 * (size_t)max_slots);
+    YQ_HIP(hipGetDevice(&s->device));
+    if (params->far_mode == YQ_FAR_FMM)
+      s->fmm_min_nodes = 0;
+    else if (params->far_mode == YQ_FAR_AUTO)
+      s->fmm_min_nodes = kFmmAutoNodes;
     *out = s.release();
   });
 }
 
 void yq_server_destroy(yq_server* s) {
   if (!s) return;
+  stop_workers(s);
   (void)hipStreamSynchronize(s->eng.stream);
   for (auto& kv : s->reqs) kv.second->pb.reset();
   delete s;
 }
 
 const char* yq_server_last_error(const yq_server* s) { return s ? s->err.c_str() : g_srv_err.c_str(); }
+
+int yq_server_set_fmm(yq_server* s, int64_t min_nodes, int32_t workers) {
+  return sguard(s, [&] {
+    YQ_REQUIRE(s, YQ_EINVAL, "null server");
+    YQ_REQUIRE(min_nodes >= 0 && workers >= 1 && workers <= 8, YQ_EINVAL,
+               "min_nodes >= 0 and 1 <= workers <= 8");
+    YQ_REQUIRE(s->next_id == 1, YQ_ESTATE, "the FMM lane is set before the first submit");
+    s->fmm_min_nodes = min_nodes;
+    s->fmm_workers = workers;
+  });
+}
 
 int yq_server_submit(yq_server* s, int32_t n, const double* center_xy, const double* angle,
                      const double* semi_axes, double kappa, int32_t label_kind, double p0,
@@ -271,13 +417,14 @@ int yq_server_submit(yq_server* s, int32_t n, const double* center_xy, const dou
     r->p0 = p0;
     r->p1 = p1;
     r->N = (int64_t)n * s->prm.panels_per_particle * Q;
-    r->est_bytes = estimate_bytes(s->prm, r->N);
+    r->fmm_lane = r->N >= s->fmm_min_nodes;
+    r->est_bytes = r->fmm_lane ? estimate_fmm_bytes(s->prm, r->N) : estimate_bytes(s->prm, r->N);
     r->t_submit = now_s();
     r->budget = s->prm.maxiter;
     *ticket = r->id;
     Request* rp = r.get();
     s->reqs[r->id] = std::move(r);
-    if (rp->N > s->capacity || rp->est_bytes > s->budget_bytes) {
+    if ((!rp->fmm_lane && rp->N > s->capacity) || rp->est_bytes > s->budget_bytes) {
       fail_request(s, rp, YQ_EADMIT, "request exceeds the node capacity or the memory budget");
       throw Error{YQ_EADMIT, "request " + std::to_string(rp->id) +
                                  " exceeds the node capacity or the memory budget"};
@@ -297,6 +444,29 @@ int yq_server_step(yq_server* s, int32_t* completed, int32_t* running, int32_t* 
     // ---- 1. admission (arrival order, first fit) ----
     for (auto it = s->queue.begin(); it != s->queue.end();) {
       Request* r = *it;
+      if (r->fmm_lane) {
+        if (s->fmm_inflight >= s->fmm_workers || s->used_bytes + r->est_bytes > s->budget_bytes) {
+          ++it;
+          continue;
+        }
+        if (s->workers.empty()) {
+          // Lane solves allocate and free device memory from other threads; a
+          // graph capture on the engine's stream must not overlap such calls,
+          // so from here on the fused iteration is launched eagerly.
+          s->eng.use_graphs = false;
+          while ((int)s->workers.size() < s->fmm_workers) s->workers.emplace_back(fmm_worker, s);
+        }
+        r->phase = RUNNING;
+        s->used_bytes += r->est_bytes;
+        ++s->fmm_inflight;
+        {
+          std::lock_guard<std::mutex> lk(s->mu);
+          s->fmm_queue.push_back(r);
+        }
+        s->cv.notify_one();
+        it = s->queue.erase(it);
+        continue;
+      }
       int slot = -1;
       for (int c = 0; c < S; ++c)
         if (!s->slots[c]) {
@@ -304,7 +474,10 @@ int yq_server_step(yq_server* s, int32_t* completed, int32_t* running, int32_t* 
           break;
         }
       int64_t off = 0;
-      if (slot < 0) break;
+      if (slot < 0) {
+        ++it;
+        continue;
+      }
       if (s->used_bytes + r->est_bytes > s->budget_bytes || !take_range(s, r->N, off)) {
         ++it;
         continue;
@@ -490,10 +663,33 @@ int yq_server_step(yq_server* s, int32_t* completed, int32_t* running, int32_t* 
       released = true;
     }
     if (released) sync_members(s);
+    // ---- FMM lane: collect finished requests ----
+    std::vector<Request*> fin;
+    {
+      std::lock_guard<std::mutex> lk(s->mu);
+      fin.swap(s->fmm_done);
+    }
+    for (Request* r : fin) {
+      --s->fmm_inflight;
+      s->used_bytes -= r->est_bytes;
+      r->info.seconds = r->t_done - r->t_submit;
+      if (r->cancel.load()) {
+        r->status = YQ_ESTATE;
+        r->err = "cancelled";
+      }
+      r->phase = (r->status == YQ_OK || r->status == YQ_ENOCONV) ? DONE : FAILED;
+      ++done_now;
+    }
     s->completed_total += done_now;
     if (completed) *completed = done_now;
-    int nrun = 0;
-    for (auto* r : s->slots) nrun += r ? 1 : 0;
+    int nbatch = 0;
+    for (auto* r : s->slots) nbatch += r ? 1 : 0;
+    const int nrun = nbatch + s->fmm_inflight;
+    if (nbatch == 0 && s->fmm_inflight > 0 && done_now == 0) {
+      // only lane solves in flight: wait a little for one instead of spinning
+      std::unique_lock<std::mutex> lk(s->mu);
+      s->cv_done.wait_for(lk, std::chrono::milliseconds(10), [&] { return !s->fmm_done.empty(); });
+    }
     if (running) *running = nrun;
     if (queued) *queued = (int)s->queue.size();
   });
@@ -540,6 +736,10 @@ int yq_server_cancel(yq_server* s, int64_t ticket) {
     Request* r = it->second.get();
     if (r->phase == QUEUED) {
       s->queue.erase(std::remove(s->queue.begin(), s->queue.end(), r), s->queue.end());
+    } else if (r->phase == RUNNING && r->fmm_lane) {
+      // a worker owns it: it ends, failed, when the server collects it
+      r->cancel.store(true);
+      return;
     } else if (r->phase == RUNNING) {
       std::vector<int> one(s->max_slots, 0);
       one[r->slot] = 1;

@@ -116,3 +116,50 @@ def test_server_admission_cancel_and_errors():
     with pytest.raises(yq.YQError) as e:
         tiny.submit(reqs[0])
     assert e.value.status == _lib.YQ_EADMIT
+
+
+def _fmm_server(**kw):
+    s = _server(**kw)
+    s.set_fmm(900, workers=2)        # requests of >= 5 particles (960+ nodes) take the FMM lane
+    return s
+
+
+def test_server_fmm_lane_matches_oracle_and_alone():
+    _torch()
+    reqs = [
+        workloads.random_ellipses(6, 12.0, 0.9, seed=31),     # FMM lane
+        workloads.random_ellipses(2, 6.0, 1.4, seed=32),      # fused batch lane
+        workloads.random_ellipses(7, 13.0, 1.2, seed=33),     # FMM lane
+        workloads.random_ellipses(3, 9.0, 0.7, seed=34),      # fused batch lane
+    ]
+    s = _fmm_server(node_capacity=20000, max_slots=4)
+    tickets = [s.submit(r) for r in reqs]
+    peak = 0
+    for _ in range(100000):
+        c, running, queued = s.step()
+        peak = max(peak, running)
+        if running == 0 and queued == 0:
+            break
+    assert peak >= 3, "both lanes must run at once"
+    for req, t in zip(reqs, tickets):
+        r = s.result(t)
+        assert r["state"] == yq.Server.DONE, r
+        assert r["info"]["residual"] <= TOL
+        d = oracle.discretize(req, Params(panels=P, qbx_order=ORDER))
+        A, Gx, Gy = oracle.build_matrices(d, gradient=True)
+        f = oracle.arc_label(d)
+        so = oracle.lu_solve(A, f)
+        assert np.abs(r["sigma"] - so).max() / np.abs(so).max() < 1e-8
+        Fo, To, _, Eo = oracle.forces_torques(d, f, oracle.surface_fields(Gx, Gy, so))
+        sc = max(np.abs(Fo).max(), np.abs(To).max(), abs(Eo))
+        assert np.abs(r["force"] - Fo).max() < 1e-7 * sc
+        assert abs(r["energy"] - Eo) < 1e-7 * abs(Eo)
+        alone = _fmm_server(node_capacity=20000, max_slots=2)
+        ta = alone.submit(req)
+        alone.run_until_idle()
+        a = alone.result(ta)
+        assert np.array_equal(a["sigma"], r["sigma"])
+        assert np.array_equal(a["force"], r["force"]) and a["energy"] == r["energy"]
+        alone.close()
+    with pytest.raises(yq.YQError):
+        s.set_fmm(0)                 # only before the first submit
