@@ -61,9 +61,16 @@ def parse():
                     help="medium: the 50-ellipse solve (default line); batch: many configurations "
                          "per fused launch; serve: Poisson-arrival continuous batching")
     ap.add_argument("--configs", type=int, default=128, help="batch: number of configurations")
-    ap.add_argument("--requests", type=int, default=96, help="serve: number of requests")
-    ap.add_argument("--rate", type=float, default=40.0, help="serve: arrival rate (1/s)")
-    ap.add_argument("--nmax", type=int, default=200, help="batch/serve: largest particle count")
+    ap.add_argument("--requests", type=int, default=2000, help="serve: number of requests")
+    ap.add_argument("--rate", type=float, default=200.0, help="serve: arrival rate (1/s)")
+    ap.add_argument("--nmax", type=int, default=None,
+                    help="batch/serve: largest particle count (default 200 batch, 2000 serve)")
+    ap.add_argument("--fmm-workers", type=int, default=3, help="serve: FMM-lane worker threads")
+    ap.add_argument("--fmm-min-nodes", type=int, default=20000,
+                    help="serve: requests of at least this many nodes take the FMM lane")
+    ap.add_argument("--fp64-requests", type=int, default=None,
+                    help="serve: requests of the trace (from the start) replayed on the FP64 "
+                         "one-at-a-time path (default all)")
     ap.add_argument("--single-baseline", type=int, default=100000,
                     help="batch: configurations also solved one at a time for comparison")
     return ap.parse_args()
@@ -162,7 +169,8 @@ def bench_batch(args):
 
     import paper_1810_04131_amd as yq
     import workloads
-    cfgs = workloads.batched_configs(args.configs, seed=0, nmax=args.nmax)
+    nmax = args.nmax or 200
+    cfgs = workloads.batched_configs(args.configs, seed=0, nmax=nmax)
     prm = yq.default_params(panels_per_particle=32, qbx_order=10, tol=1e-8,
                             precision=yq.YQ_MIXED, restart=60, maxiter=300)
     b = yq.Batch(prm)
@@ -210,7 +218,7 @@ def bench_batch(args):
         "value": pairs / t_mv, "unit": "interactions/s", "n_gpus": 1, "steps": len(lat),
         "warmup": 1, "ms_per_step": t_solve * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
-        "config": {"workload": f"batched: {len(cfgs)} configurations of 10-{args.nmax} ellipses "
+        "config": {"workload": f"batched: {len(cfgs)} configurations of 10-{nmax} ellipses "
                                f"(log-uniform), 32x16 nodes per particle, kappa~U[0.5,2], "
                                f"QBX order 10, mixed FP32/FP64 to 1e-8",
                    "configs": len(cfgs), "total_nodes": int(N.sum()),
@@ -227,28 +235,52 @@ def bench_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def _layout(req):
+    import workloads
+    return workloads.trace_particles(req)
+
+
+def trace_layouts(trace):
+    """Particle layouts of a request trace, drawn in parallel host processes."""
+    from concurrent.futures import ProcessPoolExecutor
+    workers = max(1, min(16, os.cpu_count() or 1))
+    with ProcessPoolExecutor(workers) as ex:
+        return list(ex.map(_layout, trace, chunksize=8))
+
+
 def bench_serve(args):
-    """Poisson arrivals replayed in real time against the continuous-batching server,
-    and the FP64 one-at-a-time path on the same trace (FCFS)."""
+    """Poisson arrivals replayed in real time against the continuous-batching server
+    (fused direct lane below 20,000 nodes, FMM lane above), and the FP64
+    one-at-a-time path on the same trace (FCFS)."""
     import numpy as np
     import torch
 
     import paper_1810_04131_amd as yq
     import workloads
-    trace = workloads.serving_trace(args.requests, rate=args.rate, seed=1, nmax=args.nmax)
-    parts = [workloads.trace_particles(r) for r in trace]
+    nmax = args.nmax or 2000
+    trace = workloads.serving_trace(args.requests, rate=args.rate, seed=1, nmax=nmax)
+    t_lay = time.perf_counter()
+    parts = trace_layouts(trace)
+    t_lay = time.perf_counter() - t_lay
+    print(f"# layouts of {len(parts)} requests in {t_lay:.1f} s", file=sys.stderr, flush=True)
     prm = yq.default_params(panels_per_particle=32, qbx_order=10, tol=1e-8, precision=yq.YQ_MIXED,
-                            restart=60, maxiter=300)
-    cap = int(max(p.n for p in parts) * 512 * 6)
-    srv = yq.Server(prm, node_capacity=cap, max_slots=48, mem_budget_bytes=150e9)
-    # warm-up request (graph capture, code paths)
-    w = srv.submit(parts[0])
-    srv.run_until_idle()
-    srv.release(w)
+                            restart=60, maxiter=300, far_mode=yq.YQ_FAR_AUTO)
+    srv = yq.Server(prm, node_capacity=2_000_000, max_slots=48, mem_budget_bytes=150e9)
+    thr = args.fmm_min_nodes
+    srv.set_fmm(thr, workers=args.fmm_workers)
+    # warm-up requests of both lanes (code paths, allocations)
+    small = min(range(len(parts)), key=lambda k: parts[k].n)
+    big = max(range(len(parts)), key=lambda k: parts[k].n)
+    for k in (small, big):
+        w = srv.submit(parts[k])
+        srv.run_until_idle()
+        srv.release(w)
+    print("# warm-up done", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
     pending = list(zip(trace, parts))
     tickets = []
     peak = 0
+    last_report = t0
     while True:
         now = time.perf_counter() - t0
         while pending and pending[0][0]["arrival"] <= now:
@@ -256,23 +288,34 @@ def bench_serve(args):
             tickets.append((r, srv.submit(p)))
         c, run, q = srv.step()
         peak = max(peak, run)
+        if time.perf_counter() - last_report > 30:
+            last_report = time.perf_counter()
+            print(f"# t={now:.0f}s submitted {len(tickets)} running {run} queued {q}",
+                  file=sys.stderr, flush=True)
         if run == 0 and q == 0:
             if not pending:
                 break
             time.sleep(max(0.0, min(0.002, pending[0][0]["arrival"] - now)))
     wall = time.perf_counter() - t0
-    lat = []
+    lat, lat_fmm, lat_dir = [], [], []
     worst = 0.0
-    for r, t in tickets:
+    for (r, t), p in zip(tickets, parts):
         res = srv.result(t)
         lat.append(res["latency"])
+        (lat_fmm if p.n * 512 >= thr else lat_dir).append(res["latency"])
         worst = max(worst, res["info"]["residual"])
+    print(f"# server: {len(tickets)} solves in {wall:.1f} s", file=sys.stderr, flush=True)
     # FP64 one-at-a-time path: each request solved alone, first come first served
+    # (same far-field choice per size: direct below the lane threshold, FP64 FMM above)
     p64 = yq.default_params(panels_per_particle=32, qbx_order=10, tol=1e-8, precision=yq.YQ_FP64,
                             restart=60, maxiter=300)
+    p64_fmm = yq.default_params(panels_per_particle=32, qbx_order=10, tol=1e-8,
+                                precision=yq.YQ_FP64, restart=60, maxiter=300,
+                                far_mode=yq.YQ_FAR_FMM)
+    n64 = len(parts) if args.fp64_requests is None else min(args.fp64_requests, len(parts))
     service = []
-    for p in parts:
-        pb = yq.Problem(p64)
+    for k, p in enumerate(parts[:n64]):
+        pb = yq.Problem(p64_fmm if p.n * 512 >= thr else p64)
         torch.cuda.synchronize()
         a = time.perf_counter()
         pb.set_workload(p)
@@ -281,6 +324,9 @@ def bench_serve(args):
         pb.forces(s)
         torch.cuda.synchronize()
         service.append(time.perf_counter() - a)
+        del pb
+        if (k + 1) % 200 == 0:
+            print(f"# fp64 path: {k + 1} requests", file=sys.stderr, flush=True)
     tfree = 0.0
     lat64 = []
     for r, sv in zip(trace, service):
@@ -290,17 +336,24 @@ def bench_serve(args):
     out = {
         "metric": "source-target interactions/s per matvec; solves/s + p50/p99 latency at 1e-8 rel err",
         "value": len(tickets) / wall, "unit": "solves/s", "n_gpus": 1, "steps": len(tickets),
-        "warmup": 1, "ms_per_step": wall / max(len(tickets), 1) * 1e3, "higher_is_better": True,
+        "warmup": 2, "ms_per_step": wall / max(len(tickets), 1) * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
         "config": {"workload": f"serving: Poisson arrivals at {args.rate:g}/s, {len(tickets)} "
-                               f"requests of 10-{args.nmax} ellipses (log-uniform), kappa~U[0.5,2], "
-                               f"32x16 nodes per particle, QBX order 10, mixed FP32/FP64 to 1e-8",
+                               f"requests of 10-{nmax} ellipses (log-uniform), kappa~U[0.5,2], "
+                               f"32x16 nodes per particle, QBX order 10, mixed FP32/FP64 to 1e-8; "
+                               f"fused direct lane below {thr} nodes, FMM lane "
+                               f"({args.fmm_workers} workers) above",
                    "parallelism": "single GPU"},
         "latency_ms_p50": percentile(lat, 0.5) * 1e3, "latency_ms_p99": percentile(lat, 0.99) * 1e3,
         "solves_per_s": len(tickets) / wall, "peak_concurrent": peak, "residual_max": worst,
-        "fp64_one_at_a_time": {"latency_ms_p50": percentile(lat64, 0.5) * 1e3,
+        "direct_lane": {"requests": len(lat_dir), "latency_ms_p50": percentile(lat_dir, 0.5) * 1e3,
+                        "latency_ms_p99": percentile(lat_dir, 0.99) * 1e3},
+        "fmm_lane": {"requests": len(lat_fmm), "latency_ms_p50": percentile(lat_fmm, 0.5) * 1e3,
+                     "latency_ms_p99": percentile(lat_fmm, 0.99) * 1e3},
+        "fp64_one_at_a_time": {"requests": n64,
+                               "latency_ms_p50": percentile(lat64, 0.5) * 1e3,
                                "latency_ms_p99": percentile(lat64, 0.99) * 1e3,
-                               "solves_per_s": len(service) / max(tfree, 1e-9),
+                               "solves_per_s": len(service) / max(tfree - trace[0]["arrival"], 1e-9),
                                "mean_service_ms": float(np.mean(service)) * 1e3},
     }
     print(json.dumps(out), flush=True)

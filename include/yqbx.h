@@ -71,7 +71,7 @@ typedef struct yq_params {
   int32_t pot_oversample;      /* sub-panels for off-surface targets near a panel (1..16) */
   double pot_beta;             /* off-surface near criterion, as near_beta */
   int32_t precision;           /* YQ_FP64, or YQ_MIXED: FP32 far field inside FP64 refinement */
-  int32_t far_mode;            /* YQ_FAR_DIRECT | YQ_FAR_FMM | YQ_FAR_AUTO */
+  int32_t far_mode;            /* YQ_FAR_DIRECT | YQ_FAR_FMM | YQ_FAR_AUTO (FMM from 20000 nodes) */
   int32_t fmm_order;           /* FMM expansion order (far_mode FMM) */
   int32_t fmm_leaf_max;        /* nodes per quadtree leaf (far_mode FMM) */
   double tol;                  /* GMRES: stop at ||f - A sigma||_2 / ||f||_2 <= tol */
@@ -257,7 +257,7 @@ int yq_batch_use_graphs(yq_batch* batch, int32_t enable);
  * Work of requests in flight shares every fused launch; a request's arithmetic
  * depends only on its own size, so its result is the same alone or in a mix.
  * FMM lane: requests of at least a threshold node count (params->far_mode
- * YQ_FAR_FMM: every request; YQ_FAR_AUTO: 60000 nodes; YQ_FAR_DIRECT: none;
+ * YQ_FAR_FMM: every request; YQ_FAR_AUTO: 20000 nodes; YQ_FAR_DIRECT: none;
  * yq_server_set_fmm overrides) are admitted by the memory budget alone (not the
  * arena) and solved each as a standalone problem with the FMM far field
  * (section 5's fast multipole evaluation; mixed precision with FP64 FMM

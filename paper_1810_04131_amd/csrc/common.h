@@ -15,8 +15,9 @@ constexpr int Q = 16;            // Gauss-Legendre nodes per panel
 constexpr int MAXP = 30;         // largest QBX order
 constexpr int MAXP_FMM = 48;     // largest FMM order
 // YQ_FAR_AUTO switches the inner operator (and the server lane) to the FMM from
-// this many nodes on.
-constexpr int64_t kFmmAutoNodes = 60000;
+// this many nodes on (the measured crossover of the fused direct sum and the
+// FMM on mixed-size request streams).
+constexpr int64_t kFmmAutoNodes = 20000;
 constexpr int MAXSUB = 16;       // largest oversampling factor
 constexpr double PI = 3.14159265358979323846264338327950288;
 constexpr int T_SIZE_HOST = 104;  // doubles in the FP64 coefficient table (bessel.h T_SIZE)

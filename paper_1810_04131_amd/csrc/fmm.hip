@@ -75,23 +75,32 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 // ---- translation tables ------------------------------------------------------------------
 
+// One block per table; the threads share the 4p + 1 entries.
+constexpr int TAB_BS = 128;
+
 // tg[((l * 4 + pos) * (4p + 1)) + k + 2p] = g_k(c_child - c_parent), child level l >= 1
-__global__ void tab_g_kernel(int depth, int p, double W, double kappa, double2* __restrict__ tg) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (depth + 1) * 4) return;
+__global__ __launch_bounds__(TAB_BS) void tab_g_kernel(int p, double W, double kappa,
+                                                       double2* __restrict__ tg) {
+  __shared__ double I[2 * MAXP_FMM + 1];
+  const int t = blockIdx.x;                 // l * 4 + pos
   const int l = t / 4, pos = t % 4;
   const int K = 4 * p + 1;
   double2* out = tg + (int64_t)t * K;
   if (l == 0) {
-    for (int k = 0; k < K; ++k) out[k] = make_double2(0.0, 0.0);
+    for (int k = threadIdx.x; k < K; k += TAB_BS) out[k] = make_double2(0.0, 0.0);
     return;
   }
   const double w = W / (double)(1 << l);
   const double dx = (pos & 1 ? 0.5 : -0.5) * w, dy = (pos & 2 ? 0.5 : -0.5) * w;
   const double r = sqrt(dx * dx + dy * dy), ph = atan2(dy, dx);
-  double I[2 * MAXP_FMM + 1];
-  iseries(kappa * r, 2 * p, I, 1);
-  for (int k = -2 * p; k <= 2 * p; ++k) {
+  const double x = kappa * r, tq = 0.25 * x * x;
+  for (int k = threadIdx.x; k <= 2 * p; k += TAB_BS) {
+    double pref = 1.0;                      // (x/2)^k / k!, built as in iseries
+    for (int j = 0; j < k; ++j) pref *= 0.5 * x * rcp64(double(j + 1));
+    I[k] = iorder(tq, pref, k);
+  }
+  __syncthreads();
+  for (int k = threadIdx.x - 2 * p; k <= 2 * p; k += TAB_BS) {
     double s, c;
     sincos(k * ph, &s, &c);
     const double v = I[k < 0 ? -k : k];
@@ -101,29 +110,33 @@ __global__ void tab_g_kernel(int depth, int p, double W, double kappa, double2* 
 
 // ts[((l * 49 + o) * (4p + 1)) + k + 2p] = S_k(c_t - c_s), offset o = (ox + 3) * 7 + (oy + 3)
 // of the source box relative to the target box, levels l >= 2.
-__global__ void tab_s_kernel(int depth, int p, double W, double kappa, const double* __restrict__ tab,
-                             double2* __restrict__ ts) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (depth + 1) * 49) return;
+__global__ __launch_bounds__(TAB_BS) void tab_s_kernel(int p, double W, double kappa,
+                                                       const double* __restrict__ tab,
+                                                       double2* __restrict__ ts) {
+  __shared__ double Kn[2 * MAXP_FMM + 1];
+  const int t = blockIdx.x;                 // l * 49 + o
   const int l = t / 49, o = t % 49;
   const int K = 4 * p + 1;
   double2* out = ts + (int64_t)t * K;
   const int ox = o / 7 - 3, oy = o % 7 - 3;
   if (l < 2 || (abs(ox) <= 1 && abs(oy) <= 1)) {
-    for (int k = 0; k < K; ++k) out[k] = make_double2(0.0, 0.0);
+    for (int k = threadIdx.x; k < K; k += TAB_BS) out[k] = make_double2(0.0, 0.0);
     return;
   }
   const double w = W / (double)(1 << l);
   const double dx = -ox * w, dy = -oy * w;
   const double r = sqrt(dx * dx + dy * dy), ph = atan2(dy, dx);
   const double z = kappa * r;
-  double Kn[2 * MAXP_FMM + 1];
-  double k0, k1;
-  k01_64(z, k0, k1, tab);
-  Kn[0] = k0;
-  Kn[1] = k1;
-  for (int n = 1; n < 2 * p; ++n) Kn[n + 1] = Kn[n - 1] + (2.0 * n / z) * Kn[n];
-  for (int k = -2 * p; k <= 2 * p; ++k) {
+  if (threadIdx.x == 0) {
+    // K_n by the upward recurrence (stable for K)
+    double k0, k1;
+    k01_64(z, k0, k1, tab);
+    Kn[0] = k0;
+    Kn[1] = k1;
+    for (int n = 1; n < 2 * p; ++n) Kn[n + 1] = Kn[n - 1] + (2.0 * n / z) * Kn[n];
+  }
+  __syncthreads();
+  for (int k = threadIdx.x - 2 * p; k <= 2 * p; k += TAB_BS) {
     double s, c;
     sincos(k * ph, &s, &c);
     const double v = Kn[k < 0 ? -k : k];
@@ -895,8 +908,8 @@ void Fmm::set_order(int q, const double* tab, hipStream_t s) {
   const int K = 4 * p + 1;
   tg.alloc((size_t)(depth + 1) * 4 * K);
   ts.alloc((size_t)(depth + 1) * 49 * K);
-  tab_g_kernel<<<((depth + 1) * 4 + 63) / 64, 64, 0, s>>>(depth, p, W, kappa, tg.p);
-  tab_s_kernel<<<((depth + 1) * 49 + 63) / 64, 64, 0, s>>>(depth, p, W, kappa, tab, ts.p);
+  tab_g_kernel<<<(depth + 1) * 4, TAB_BS, 0, s>>>(p, W, kappa, tg.p);
+  tab_s_kernel<<<(depth + 1) * 49, TAB_BS, 0, s>>>(p, W, kappa, tab, ts.p);
   YQ_HIP(hipGetLastError());
   R16 = ((2 * (p + 1) + 15) / 16) * 16;
   if (use_mfma) {

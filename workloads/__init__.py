@@ -77,11 +77,15 @@ def _sample_spacing(axes, m=_NSAMPLE):
     return float(axes[0]) * 2.0 * np.pi / m
 
 
-def _place(rng, n, box, axes_fn, gap, max_tries=200000):
+def _place(rng, n, box, axes_fn, gap, amax, max_tries=200000):
+    """Rejection sampling; placed ellipses are looked up through a grid of cells of
+    side >= 2 amax + gap, so only the 3 x 3 cells around a candidate are checked."""
     centers: List[np.ndarray] = []
     angles: List[float] = []
     axes: List[np.ndarray] = []
     samples: List[np.ndarray] = []
+    cell = 2.0 * amax + gap + 1e-6
+    grid: dict = {}
     tries = 0
     while len(centers) < n:
         tries += 1
@@ -91,26 +95,30 @@ def _place(rng, n, box, axes_fn, gap, max_tries=200000):
         lo = ax[0] + 0.5 * gap
         c = rng.uniform(lo, box - lo, size=2)
         th = rng.uniform(0.0, 2.0 * np.pi)
+        gx, gy = int(c[0] // cell), int(c[1] // cell)
+        near = sorted(j for ix in (gx - 1, gx, gx + 1) for iy in (gy - 1, gy, gy + 1)
+                      for j in grid.get((ix, iy), ()))
         ok = True
-        if centers:
-            C = np.asarray(centers)
-            A = np.asarray(axes)[:, 0]
-            d = np.hypot(C[:, 0] - c[0], C[:, 1] - c[1])
-            cand = np.nonzero(d < A + ax[0] + gap + 1e-6)[0]
-            B = np.asarray(axes)[:, 1]
-            if cand.size and np.any(d[cand] < B[cand] + ax[1] + gap):
-                ok = False      # the inscribed circles alone are closer than the gap
-                cand = cand[:0]
-            if cand.size:
-                sp = _boundary_samples(c, th, ax)
-                for j in cand:
-                    dd = np.sqrt(((sp[:, None, :] - samples[j][None, :, :]) ** 2).sum(-1)).min()
-                    slack = 0.5 * (_sample_spacing(ax) + _sample_spacing(axes[j]))
-                    # the sampled minimum can only overestimate the true one
-                    if dd - slack < gap + 1e-3:
-                        ok = False
-                        break
+        sel = []
+        cx, cy, a0, b0 = float(c[0]), float(c[1]), float(ax[0]), float(ax[1])
+        for j in near:
+            d = math.hypot(centers[j][0] - cx, centers[j][1] - cy)
+            if d < axes[j][0] + a0 + gap + 1e-6:
+                if d < axes[j][1] + b0 + gap:
+                    ok = False  # the inscribed circles alone are closer than the gap
+                    break
+                sel.append(j)
+        if ok and sel:
+            sp = _boundary_samples(c, th, ax)
+            for j in sel:
+                dd = np.sqrt(((sp[:, None, :] - samples[j][None, :, :]) ** 2).sum(-1)).min()
+                slack = 0.5 * (_sample_spacing(ax) + _sample_spacing(axes[j]))
+                # the sampled minimum can only overestimate the true one
+                if dd - slack < gap + 1e-3:
+                    ok = False
+                    break
         if ok:
+            grid.setdefault((gx, gy), []).append(len(centers))
             centers.append(c)
             angles.append(th)
             axes.append(ax)
@@ -129,10 +137,12 @@ def random_ellipses(n: int, box: float, kappa: float, seed: int, gap: float = 0.
     if axes_range is None:
         fixed = np.asarray(axes, dtype=np.float64)
         axes_fn = lambda r: fixed
+        amax = float(fixed[0])
     else:
         (alo, ahi), (blo, bhi) = axes_range
         axes_fn = lambda r: np.array([r.uniform(alo, ahi), r.uniform(blo, bhi)])
-    c, th, ax = _place(rng, n, box, axes_fn, gap)
+        amax = float(ahi)
+    c, th, ax = _place(rng, n, box, axes_fn, gap, amax)
     return Particles(c, th, ax, float(kappa), name or f"{n} ellipses, box {box}, seed {seed}")
 
 
