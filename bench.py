@@ -65,7 +65,11 @@ def parse():
     ap.add_argument("--rate", type=float, default=200.0, help="serve: arrival rate (1/s)")
     ap.add_argument("--nmax", type=int, default=None,
                     help="batch/serve: largest particle count (default 200 batch, 2000 serve)")
-    ap.add_argument("--fmm-workers", type=int, default=3, help="serve: FMM-lane worker threads")
+    ap.add_argument("--fmm-workers", type=int, default=3,
+                    help="serve/batch: FMM-lane worker threads")
+    ap.add_argument("--batch-lane", choices=["hybrid", "fused"], default="hybrid",
+                    help="batch: hybrid = configurations from --fmm-min-nodes on take the FMM "
+                         "lane; fused = every configuration in the fused direct engine")
     ap.add_argument("--fmm-min-nodes", type=int, default=20000,
                     help="serve: requests of at least this many nodes take the FMM lane")
     ap.add_argument("--fp64-requests", type=int, default=None,
@@ -171,27 +175,43 @@ def bench_batch(args):
     import workloads
     nmax = args.nmax or 200
     cfgs = workloads.batched_configs(args.configs, seed=0, nmax=nmax)
+    hybrid = args.batch_lane == "hybrid"
+    thr = args.fmm_min_nodes if hybrid else None
     prm = yq.default_params(panels_per_particle=32, qbx_order=10, tol=1e-8,
                             precision=yq.YQ_MIXED, restart=60, maxiter=300)
+    log = lambda msg: print(f"# {msg}", file=sys.stderr, flush=True)
+    log(f"{len(cfgs)} configurations drawn")
     b = yq.Batch(prm)
+    if hybrid:
+        b.set_fmm(thr, workers=args.fmm_workers)
     t0 = time.perf_counter()
     b.set_configs(cfgs)
     t_setup = time.perf_counter() - t0
+    log(f"set-up {t_setup:.1f} s, {b.total} nodes")
     pblk, fwant = b.autotune()
+    log(f"autotuned: persistent blocks {pblk}, far_want {fwant}")
     b.set_boundary_data(b.boundary_label())
     b.solve()                                   # warm-up (captures the iteration graph)
+    log("warm-up solve done")
     lat = []
-    for _ in range(max(args.steps, 1)):
+    for k in range(max(args.steps, 1)):
         t0 = time.perf_counter()
         sig, infos = b.solve()
         lat.append(time.perf_counter() - t0)
+        log(f"timed solve {k + 1}: {lat[-1]:.2f} s")
     F, T, E = b.forces(sig)
     torch.cuda.synchronize()
     N = np.diff(b.offsets).astype(float)
     its = np.array([i["iterations"] for i in infos])
     ref = np.array([i["outer_steps"] for i in infos])
     resid = max(i["residual"] for i in infos)
-    # one fused FP32 far-field pass evaluates sum_c N_c^2 pairs; time it alone
+    # one fused FP32 far-field pass evaluates sum_c N_c^2 pairs over the engine's
+    # members; time it alone on a fused-only batch of the same configurations
+    if hybrid:
+        b.close()
+        b = yq.Batch(prm)
+        b.set_configs(cfgs)
+        b.autotune()
     s = torch.randn(b.total, dtype=torch.float64, device="cuda")
     b.apply_operator(s, yq.YQ_MIXED)
     torch.cuda.synchronize()
@@ -201,12 +221,18 @@ def bench_batch(args):
     torch.cuda.synchronize()
     t_mv = (time.perf_counter() - t0) / 3
     pairs = float((N * N).sum())
+    b.close()
     t_solve = percentile(lat, 0.5)
-    # one at a time, same solver, on the first configurations
+    # one at a time, same solver and per-size far field, on the first configurations
     k1 = min(args.single_baseline, len(cfgs))
     t_single = 0.0
-    for c in cfgs[:k1]:
-        pb = yq.Problem(prm)
+    prm_fmm = yq.default_params(panels_per_particle=32, qbx_order=10, tol=1e-8,
+                                precision=yq.YQ_MIXED, restart=60, maxiter=300,
+                                far_mode=yq.YQ_FAR_FMM)
+    for k, c in enumerate(cfgs[:k1]):
+        if k % 128 == 0:
+            log(f"one at a time: {k} of {k1}")
+        pb = yq.Problem(prm_fmm if hybrid and c.n * 512 >= thr else prm)
         t0 = time.perf_counter()
         pb.set_workload(c)
         pb.set_boundary_data(pb.boundary_label())
@@ -220,7 +246,10 @@ def bench_batch(args):
         "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
         "config": {"workload": f"batched: {len(cfgs)} configurations of 10-{nmax} ellipses "
                                f"(log-uniform), 32x16 nodes per particle, kappa~U[0.5,2], "
-                               f"QBX order 10, mixed FP32/FP64 to 1e-8",
+                               f"QBX order 10, mixed FP32/FP64 to 1e-8; "
+                               + (f"fused direct engine below {thr} nodes, FMM lane "
+                                  f"({args.fmm_workers} workers) above" if hybrid
+                                  else "every configuration in the fused direct engine"),
                    "configs": len(cfgs), "total_nodes": int(N.sum()),
                    "parallelism": "single GPU"},
         "solves_per_s": len(cfgs) / t_solve,

@@ -198,6 +198,12 @@ int yq_eval_potential(yq_problem* prob, const double* sigma, int64_t M, const do
  * fused correction, batched CGS2 Arnoldi, device-side Givens), captured once as
  * a hipGraph and replayed.  A configuration's arithmetic depends only on its own
  * size, so its result is bitwise the same alone (a batch of one) or in a mix.
+ * FMM lane: configurations of at least a threshold node count (params->far_mode
+ * YQ_FAR_FMM: all; YQ_FAR_AUTO: 20000 nodes; YQ_FAR_DIRECT: none;
+ * yq_batch_set_fmm overrides) are not engine members: each is a standalone
+ * problem with the FMM far field, solved by worker threads (largest first, one
+ * stream of default priority each) while the engine solves the rest; the
+ * engine then launches its iteration eagerly instead of replaying a graph.
  * The batch owns a HIP stream of default priority; every batch call is
  * synchronous (returns after its work is done) and reads its device inputs when
  * called, so the caller must have finished writing them. */
@@ -206,6 +212,10 @@ typedef struct yq_batch yq_batch;
 int yq_batch_create(const yq_params* params, yq_batch** out);
 void yq_batch_destroy(yq_batch* batch);
 const char* yq_batch_last_error(const yq_batch* batch);
+
+/* FMM lane threshold (nodes, >= 0) and worker count (1..8); before
+ * yq_batch_set_configs (YQ_ESTATE after). */
+int yq_batch_set_fmm(yq_batch* batch, int64_t min_nodes, int32_t workers);
 
 /* nparticles: host [nconf]; center_xy, angle, semi_axes: host, all configurations'
  * particles concatenated in order (layout as yq_set_particles); kappa: host [nconf].

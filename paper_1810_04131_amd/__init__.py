@@ -206,6 +206,11 @@ class Batch:
     def _sync(self):
         self.torch.cuda.synchronize(self.device)
 
+    def set_fmm(self, min_nodes, workers=3):
+        """Configurations of at least min_nodes nodes take the FMM lane (before set_configs)."""
+        self._check(self.lib.yq_batch_set_fmm(self.h, int(min_nodes), int(workers)))
+        return self
+
     def _f64(self, *shape):
         return self.torch.empty(*shape, dtype=self.torch.float64, device=self.device)
 

@@ -48,6 +48,7 @@ struct Engine {
   int64_t T = 0;            // arena capacity (nodes)
   std::vector<Member> members;
 
+  DevBuf<double> tab64;       // FP64 Bessel coefficients (shared by all configurations)
   DevBuf<ConfDev> conf;
   DevBuf<int4> items;
   DevBuf<int2> kblk;

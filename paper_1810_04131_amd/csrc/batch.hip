@@ -40,11 +40,14 @@ constexpr int KB2 = 256;   // Krylov block size
 
 // ---- fused far field ----------------------------------------------------------------------
 
+// tab: the FP64 Bessel coefficient table (the same constants for every
+// configuration), passed as an argument so that it stays in scalar registers.
 __global__ __launch_bounds__(BB) void bfar64_kernel(const ConfDev* __restrict__ cf,
                                                     const int4* __restrict__ items, int nitems,
                                                     const int* __restrict__ mask,
                                                     const double* __restrict__ V,
-                                                    const int* __restrict__ col, int64_t T) {
+                                                    const int* __restrict__ col, int64_t T,
+                                                    const double* __restrict__ tab) {
   __shared__ double2 sxy[BB];
   __shared__ double2 sq[BB];
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
@@ -70,7 +73,7 @@ __global__ __launch_bounds__(BB) void bfar64_kernel(const ConfDev* __restrict__ 
       }
       __syncthreads();
       const int nb = (int)min((int64_t)BB, j1 - jb);
-      acc = far64_tile(xi, yi, sxy, sq, nb, cd.kap2, cd.tab, acc);
+      acc = far64_tile(xi, yi, sxy, sq, nb, cd.kap2, tab, acc);
     }
     if (i < N) cd.part64[(int64_t)w.z * N + i] = acc;
   }
@@ -317,6 +320,11 @@ void Engine::init(const yq_params& p) {
     YQ_HIP(hipStreamCreate(&stream));  // default priority
     own_stream = true;
   }
+  std::vector<double> t(T_SIZE_HOST);
+  fill_tab64(t.data());
+  tab64.alloc(t.size());
+  YQ_HIP(hipMemcpyAsync(tab64.p, t.data(), t.size() * sizeof(double), hipMemcpyHostToDevice, stream));
+  YQ_HIP(hipStreamSynchronize(stream));
 }
 
 // Rebuilds the descriptors, work lists and per-configuration reduction blocks.
@@ -433,7 +441,8 @@ void Engine::matvec(int prec, const int* mask, const double* Vin, const int* col
   if (prec == YQ_MIXED)
     bfar32_kernel<<<grid_blocks(), BB, 0, stream>>>(conf.p, items.p, nitems, mask, Vin, col, T);
   else
-    bfar64_kernel<<<grid_blocks(), BB, 0, stream>>>(conf.p, items.p, nitems, mask, Vin, col, T);
+    bfar64_kernel<<<grid_blocks(), BB, 0, stream>>>(conf.p, items.p, nitems, mask, Vin, col, T,
+                                                    tab64.p);
   YQ_HIP(hipGetLastError());
   bfinish_kernel<<<nb256(T), 256, 0, stream>>>(conf.p, node_conf.p, T, mask, prec == YQ_MIXED, Vin,
                                                col, out);

@@ -1,9 +1,18 @@
 // C ABI of the batch engine (include/yqbx.h, "Batched solves").
+//
+// Configurations below the FMM threshold are members of the fused engine (one
+// persistent far-field launch per GMRES iteration for all of them); those at or
+// above it get their own problem with the FMM far field and are solved by
+// worker threads, largest first, each on its own stream, while the engine runs.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
+#include <limits>
 #include <memory>
+#include <numeric>
 #include <string>
+#include <thread>
 
 #include "batch.h"
 #include "common.h"
@@ -21,6 +30,15 @@ struct yq_batch {
   std::string err;
   bool ready = false;
   bool have_f = false;
+  // FMM lane
+  int64_t fmm_min_nodes = std::numeric_limits<int64_t>::max();
+  int fmm_workers = 3;
+  std::vector<int> direct_idx, fmm_idx;   // configuration indices of each lane
+  std::vector<hipStream_t> streams;       // one per worker (default priority)
+  int device = 0;
+  ~yq_batch() {
+    for (hipStream_t s : streams) (void)hipStreamDestroy(s);
+  }
 };
 
 namespace {
@@ -52,8 +70,8 @@ void require(const yq_batch* b) {
 }
 
 void rebuild_plans(yq_batch* b) {
-  for (auto& p : b->probs) {
-    yq_problem* pb = p.get();
+  for (int c : b->direct_idx) {
+    yq_problem* pb = b->probs[c].get();
     pb->far_want = b->far_want;
     pb->fp = far_plan(pb->N, pb->N, 256, b->far_want);
     pb->partial.alloc((size_t)pb->fp.chunks * pb->N);
@@ -76,6 +94,11 @@ int yq_batch_create(const yq_params* params, yq_batch** out) {
     auto b = std::make_unique<yq_batch>();
     b->prm = *params;
     b->eng.init(*params);
+    YQ_HIP(hipGetDevice(&b->device));
+    if (params->far_mode == YQ_FAR_FMM)
+      b->fmm_min_nodes = 0;
+    else if (params->far_mode == YQ_FAR_AUTO)
+      b->fmm_min_nodes = kFmmAutoNodes;
     *out = b.release();
   });
 }
@@ -98,18 +121,29 @@ int yq_batch_set_configs(yq_batch* b, int32_t nconf, const int32_t* np, const do
     b->have_f = false;
     b->probs.clear();
     b->eng.members.clear();
+    b->direct_idx.clear();
+    b->fmm_idx.clear();
     b->offsets.assign(nconf + 1, 0);
     b->poffsets.assign(nconf + 1, 0);
     int64_t pofs = 0;
     for (int c = 0; c < nconf; ++c) {
       YQ_REQUIRE(np[c] >= 1, YQ_EINVAL, "configuration " + std::to_string(c) + " has no particles");
+      const int64_t Nc = (int64_t)np[c] * b->prm.panels_per_particle * Q;
+      const bool lane = Nc >= b->fmm_min_nodes;
+      yq_params p = b->prm;
+      if (lane) p.far_mode = YQ_FAR_FMM;
       yq_problem* pb = nullptr;
-      int st = yq_create(&b->prm, &pb);
+      int st = yq_create(&p, &pb);
       YQ_REQUIRE(st == YQ_OK, st, "yq_create failed");
       b->probs.emplace_back(pb, yq_destroy);
-      pb->batch_member = true;
       pb->far_want = b->far_want;
-      pb->stream = b->eng.stream;
+      if (lane) {
+        b->fmm_idx.push_back(c);
+      } else {
+        pb->batch_member = true;
+        pb->stream = b->eng.stream;
+        b->direct_idx.push_back(c);
+      }
       st = yq_set_particles(pb, np[c], center_xy + 2 * pofs, angle + pofs, semi_axes + 2 * pofs,
                             kappa[c]);
       YQ_REQUIRE(st == YQ_OK, st,
@@ -119,8 +153,19 @@ int yq_batch_set_configs(yq_batch* b, int32_t nconf, const int32_t* np, const do
       b->poffsets[c + 1] = pofs;
     }
     b->eng.T = b->offsets[nconf];
-    for (int c = 0; c < nconf; ++c) b->eng.members.push_back(Member{b->probs[c].get(), b->offsets[c]});
-    b->eng.rebuild();
+    for (int c : b->direct_idx) b->eng.members.push_back(Member{b->probs[c].get(), b->offsets[c]});
+    if (!b->direct_idx.empty()) b->eng.rebuild();
+    // FMM lane: largest first, one stream per worker
+    std::sort(b->fmm_idx.begin(), b->fmm_idx.end(), [&](int x, int y) {
+      const int64_t nx = b->offsets[x + 1] - b->offsets[x], ny = b->offsets[y + 1] - b->offsets[y];
+      return nx != ny ? nx > ny : x < y;
+    });
+    const int nw = std::min<int>(b->fmm_workers, (int)b->fmm_idx.size());
+    while ((int)b->streams.size() < nw) {
+      hipStream_t s = nullptr;
+      YQ_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+      b->streams.push_back(s);
+    }
     b->ready = true;
   });
 }
@@ -149,8 +194,9 @@ int yq_batch_set_boundary_data(yq_batch* b, const double* f) {
   return bguard(b, [&] {
     require(b);
     YQ_REQUIRE(f, YQ_EINVAL, "null f");
-    YQ_HIP(hipMemcpyAsync(b->eng.f.p, f, b->eng.T * sizeof(double), hipMemcpyDeviceToDevice,
-                          b->eng.stream));
+    if (!b->direct_idx.empty())     // the engine holds f only when it has members
+      YQ_HIP(hipMemcpyAsync(b->eng.f.p, f, b->eng.T * sizeof(double), hipMemcpyDeviceToDevice,
+                            b->eng.stream));
     for (size_t c = 0; c < b->probs.size(); ++c) {
       int st = yq_set_boundary_data(b->probs[c].get(), f + b->offsets[c]);
       YQ_REQUIRE(st == YQ_OK, st, yq_last_error(b->probs[c].get()));
@@ -166,9 +212,17 @@ int yq_batch_apply_operator(yq_batch* b, const double* sigma, double* out, int32
     YQ_REQUIRE(sigma && out && sigma != out, YQ_EINVAL, "null or aliased argument");
     YQ_REQUIRE(precision == YQ_FP64 || precision == YQ_MIXED, YQ_EINVAL, "bad precision");
     Engine& e = b->eng;
-    std::vector<int> all(e.members.size(), 1);
-    e.upload_mask(e.inc, all);
-    e.matvec(precision, e.inc.p, sigma, nullptr, out);
+    if (!b->direct_idx.empty()) {
+      std::vector<int> all(e.members.size(), 1);
+      e.upload_mask(e.inc, all);
+      e.matvec(precision, e.inc.p, sigma, nullptr, out);
+    }
+    for (int c : b->fmm_idx) {
+      yq_problem* pb = b->probs[c].get();
+      const int st = yq_apply_operator(pb, sigma + b->offsets[c], out + b->offsets[c], precision);
+      YQ_REQUIRE(st == YQ_OK, st, yq_last_error(pb));
+      YQ_HIP(hipStreamSynchronize(pb->stream));
+    }
     YQ_HIP(hipStreamSynchronize(e.stream));
   });
 }
@@ -179,12 +233,55 @@ int yq_batch_solve(yq_batch* b, double* sigma, yq_solve_info* info) {
     require(b);
     YQ_REQUIRE(sigma, YQ_EINVAL, "null sigma");
     YQ_REQUIRE(b->have_f, YQ_ESTATE, "boundary data not set");
-    std::vector<yq_solve_info> inf;
-    b->eng.solve(inf, sigma);
-    YQ_HIP(hipStreamSynchronize(b->eng.stream));
-    for (size_t c = 0; c < inf.size(); ++c) {
-      if (info) info[c] = inf[c];
-      if (!(inf[c].residual <= b->prm.tol)) status = YQ_ENOCONV;
+    const int nconf = (int)b->probs.size();
+    std::vector<yq_solve_info> all(nconf);
+    // FMM lane on worker threads
+    const int nf = (int)b->fmm_idx.size();
+    std::vector<int> codes(nf, YQ_OK);
+    std::vector<std::string> errs(nf);
+    std::atomic<int> next{0};
+    struct Joiner {
+      std::vector<std::thread> t;
+      ~Joiner() {
+        for (auto& x : t)
+          if (x.joinable()) x.join();
+      }
+    } workers;
+    for (size_t w = 0; w < b->streams.size() && nf > 0; ++w) {
+      workers.t.emplace_back([&, w] {
+        (void)hipSetDevice(b->device);
+        for (int k = next++; k < nf; k = next++) {
+          const int c = b->fmm_idx[k];
+          yq_problem* pb = b->probs[c].get();
+          pb->stream = b->streams[w];
+          const int st = yq_solve(pb, nullptr, sigma + b->offsets[c], &all[c]);
+          codes[k] = st;
+          if (st != YQ_OK && st != YQ_ENOCONV) errs[k] = yq_last_error(pb);
+        }
+      });
+    }
+    // fused lane on this thread; no graph capture while the workers allocate
+    if (!b->direct_idx.empty()) {
+      const bool graphs = b->eng.use_graphs;
+      if (nf > 0) b->eng.use_graphs = false;
+      std::vector<yq_solve_info> inf;
+      try {
+        b->eng.solve(inf, sigma);
+        YQ_HIP(hipStreamSynchronize(b->eng.stream));
+      } catch (...) {
+        b->eng.use_graphs = graphs;
+        throw;
+      }
+      b->eng.use_graphs = graphs;
+      for (size_t k = 0; k < inf.size(); ++k) all[b->direct_idx[k]] = inf[k];
+    }
+    for (auto& x : workers.t) x.join();
+    for (int k = 0; k < nf; ++k)
+      YQ_REQUIRE(codes[k] == YQ_OK || codes[k] == YQ_ENOCONV, codes[k],
+                 "configuration " + std::to_string(b->fmm_idx[k]) + ": " + errs[k]);
+    for (int c = 0; c < nconf; ++c) {
+      if (info) info[c] = all[c];
+      if (!(all[c].residual <= b->prm.tol)) status = YQ_ENOCONV;
     }
   });
   if (rc != YQ_OK) return rc;
@@ -208,6 +305,17 @@ int yq_batch_forces(yq_batch* b, const double* sigma, double gamma, double* forc
   });
 }
 
+int yq_batch_set_fmm(yq_batch* b, int64_t min_nodes, int32_t workers) {
+  return bguard(b, [&] {
+    YQ_REQUIRE(b, YQ_EINVAL, "null batch");
+    YQ_REQUIRE(min_nodes >= 0 && workers >= 1 && workers <= 8, YQ_EINVAL,
+               "min_nodes >= 0 and 1 <= workers <= 8");
+    YQ_REQUIRE(!b->ready, YQ_ESTATE, "the FMM lane is set before yq_batch_set_configs");
+    b->fmm_min_nodes = min_nodes;
+    b->fmm_workers = workers;
+  });
+}
+
 int yq_batch_use_graphs(yq_batch* b, int32_t enable) {
   if (!b) return YQ_EINVAL;
   b->eng.use_graphs = enable != 0;
@@ -218,6 +326,11 @@ int yq_batch_autotune(yq_batch* b, int32_t* persist_out, int32_t* want_out) {
   return bguard(b, [&] {
     require(b);
     Engine& e = b->eng;
+    if (b->direct_idx.empty()) {   // nothing runs through the fused engine
+      if (persist_out) *persist_out = e.persist_blocks;
+      if (want_out) *want_out = b->far_want;
+      return;
+    }
     const int persist_c[] = {1024, 2048, 4096, 8192};
     const int want_c[] = {2048, 4096, 8192};
     std::vector<int> all(e.members.size(), 1);

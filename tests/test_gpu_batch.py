@@ -159,3 +159,50 @@ def test_batch_autotune_keeps_results_within_tolerance(oracles):
     for c, o in enumerate(oracles):
         s = slice(int(b.offsets[c]), int(b.offsets[c + 1]))
         assert _rel(sig[s], o["sigma"]) < 1e-8
+
+
+def test_batch_fmm_lane_matches_oracle_single_and_direct_batch(oracles):
+    torch = _torch()
+    cfgs = _configs()
+    prm = dict(panels_per_particle=P, qbx_order=ORDER, tol=1e-10, precision=1)
+    b = yq.Batch(yq.default_params(**prm))
+    b.set_fmm(5 * P * 16, workers=2)        # the 5-particle configuration takes the FMM lane
+    b.set_configs(cfgs)
+    with pytest.raises(yq.YQError):
+        b.set_fmm(0)                         # only before set_configs
+    b.set_boundary_data(b.boundary_label())
+    sig, infos = b.solve()
+    sig = _np(sig)
+    direct = _batch(cfgs, **{k: v for k, v in prm.items() if k not in ("panels_per_particle", "qbx_order")})
+    direct.set_boundary_data(direct.boundary_label())
+    sd, _ = direct.solve()
+    sd = _np(sd)
+    x = np.concatenate([workloads.random_density(o["d"].N, 40 + c) for c, o in enumerate(oracles)])
+    op = _np(b.apply_operator(x))
+    for c, o in enumerate(oracles):
+        s = slice(int(b.offsets[c]), int(b.offsets[c + 1]))
+        assert infos[c]["residual"] <= 1e-10, (c, infos[c])
+        assert _rel(sig[s], o["sigma"]) < 1e-8, c
+        assert _rel(op[s], o["A"] @ x[s]) < 1e-12, c
+        if c == 2:
+            # the lane's configuration is exactly a standalone FMM solve
+            pb = yq.Problem(yq.default_params(far_mode=yq.YQ_FAR_FMM, **prm))
+            pb.set_workload(cfgs[c])
+            pb.set_boundary_data(pb.boundary_label())
+            ss, _ = pb.solve()
+            assert np.array_equal(_np(ss), sig[s])
+        else:
+            # the engine members are unchanged by the lane next to them
+            assert np.array_equal(sd[s], sig[s]), c
+    F, T, E = b.forces(torch.as_tensor(sig, device="cuda"))
+    Fd, Td, Ed = direct.forces(torch.as_tensor(sig, device="cuda"))
+    sc = max(np.abs(_np(Fd)).max(), np.abs(_np(Td)).max())
+    assert np.abs(_np(F) - _np(Fd)).max() < 1e-9 * sc and np.abs(_np(T) - _np(Td)).max() < 1e-9 * sc
+    # every configuration in the lane (no engine members)
+    allf = yq.Batch(yq.default_params(far_mode=yq.YQ_FAR_FMM, **prm))
+    allf.set_configs(cfgs[:2])
+    allf.set_boundary_data(allf.boundary_label())
+    sa, ia = allf.solve()
+    for c in range(2):
+        s = slice(int(allf.offsets[c]), int(allf.offsets[c + 1]))
+        assert ia[c]["residual"] <= 1e-10 and _rel(_np(sa)[s], oracles[c]["sigma"]) < 1e-8
