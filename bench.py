@@ -39,7 +39,8 @@ sys.path.insert(0, ROOT)
 #         accumulate (1)                                                    = 113
 F_DL32 = 36
 F_DL64 = 113
-SRC_FOR_COUNTERS = ["paper_1810_04131_amd/csrc/farfield.hip", "paper_1810_04131_amd/csrc/bessel.h",
+SRC_FOR_COUNTERS = ["paper_1810_04131_amd/csrc/farfield.hip",
+                    "paper_1810_04131_amd/csrc/farfield_core.h", "paper_1810_04131_amd/csrc/bessel.h",
                     "paper_1810_04131_amd/csrc/bessel_tables.h"]
 COUNTERS_FILE = "profiles/far32_kernel_50ellipses_N25600_counters.txt"
 PEAK_FP32 = 157.3e12   # published MI355X FP32 vector peak (needs packed FP32)

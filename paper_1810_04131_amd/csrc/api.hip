@@ -656,7 +656,8 @@ int yq_solve(yq_problem* pb, const double* sigma0, double* sigma, yq_solve_info*
       YQ_HIP(hipMemcpyAsync(sigma, sigma0, N * sizeof(double), hipMemcpyDeviceToDevice, s));
     bool zero = sigma0 == nullptr;
     bool conv = false;
-    double* r = pb->kd.p;  // refinement residual
+    bool r_current = false;  // r holds f - A sigma (FP64 operator) for the current sigma
+    double* r = pb->kd.p;    // refinement residual
     if (pb->prm.precision == YQ_FP64) {
       GmresResult R = gmres(pb, OP_RESID, pb->f.p, sigma, zero, pb->prm.tol, pb->prm.maxiter);
       inf.iterations = R.iterations;
@@ -681,6 +682,7 @@ int yq_solve(yq_problem* pb, const double* sigma0, double* sigma, yq_solve_info*
           launch_axpby(-1.0, pb->kw.p, 1.0, pb->f.p, r, N, s);
           rel = fnorm > 0.0 ? std::sqrt(dot_host(pb, r, r)) / fnorm : 0.0;
         }
+        r_current = true;
         if (rel <= pb->prm.tol) {
           conv = true;
           break;
@@ -693,12 +695,15 @@ int yq_solve(yq_problem* pb, const double* sigma0, double* sigma, yq_solve_info*
         inf.matvecs_fp32 += R.matvecs;
         budget -= R.iterations;
         launch_axpby(1.0, delta.p, 1.0, sigma, sigma, N, s);
+        r_current = false;
       }
     }
-    // final FP64 residual
-    apply_resid(pb, sigma, pb->kw.p);
-    ++inf.matvecs_fp64;
-    launch_axpby(-1.0, pb->kw.p, 1.0, pb->f.p, r, N, s);
+    // final FP64 residual (the refinement loop's last one when sigma has not moved since)
+    if (!r_current) {
+      apply_resid(pb, sigma, pb->kw.p);
+      ++inf.matvecs_fp64;
+      launch_axpby(-1.0, pb->kw.p, 1.0, pb->f.p, r, N, s);
+    }
     const double fn = std::sqrt(dot_host(pb, pb->f.p, pb->f.p));
     inf.residual = fn > 0.0 ? std::sqrt(dot_host(pb, r, r)) / fn : 0.0;
     if (pb->prm.precision == YQ_MIXED) conv = inf.residual <= pb->prm.tol;

@@ -652,6 +652,8 @@ void Engine::solve(std::vector<yq_solve_info>& info, double* x_out) {
   std::vector<int> all(nc, 1), iters(nc, 0), budget(nc, prm.maxiter), conv_c(nc, 0);
   for (int c = 0; c < nc; ++c) all[c] = members[c].pb ? 1 : 0;
   int mv = 0;
+  // residual of the final iterate, when the refinement loop computed it last (-1: unknown)
+  std::vector<double> res_known(nc, -1.0);
   upload_mask(inc, all);
   dots(inc.p, f.p, f.p);
   std::vector<double> fn = read_nrm();
@@ -688,6 +690,7 @@ void Engine::solve(std::vector<yq_solve_info>& info, double* x_out) {
         if (!run[c]) continue;
         if (rel[c] <= prm.tol || budget[c] <= 0) {
           run[c] = 0;
+          if (outer > 0) res_known[c] = rel[c];   // x has not moved since
           continue;
         }
         ++nrun;
@@ -708,16 +711,30 @@ void Engine::solve(std::vector<yq_solve_info>& info, double* x_out) {
     }
     for (int c = 0; c < nc; ++c) info[c].iterations = iters[c];
   }
-  // true FP64 residual of every member
-  upload_mask(inc, all);
-  matvec(YQ_FP64, inc.p, x_out, nullptr, tmp.p);
-  axpby(inc.p, 1.0, f.p, -1.0, tmp.p, r.p);
-  dots(inc.p, r.p, r.p);
-  std::vector<double> rn = read_nrm();
+  // true FP64 residual of every member whose final iterate has none yet
+  std::vector<int> need(nc, 0);
+  int nneed = 0;
+  for (int c = 0; c < nc; ++c)
+    if (all[c] && res_known[c] < 0.0) {
+      need[c] = 1;
+      ++nneed;
+    }
+  std::vector<double> rn(nc, 0.0);
+  if (nneed) {
+    upload_mask(inc, need);
+    matvec(YQ_FP64, inc.p, x_out, nullptr, tmp.p);
+    axpby(inc.p, 1.0, f.p, -1.0, tmp.p, r.p);
+    dots(inc.p, r.p, r.p);
+    rn = read_nrm();
+  }
   const double sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   for (int c = 0; c < nc; ++c) {
-    info[c].residual = fn[c] > 0.0 ? std::sqrt(std::max(rn[c], 0.0)) / fn[c] : 0.0;
-    info[c].matvecs_fp64 += 1;
+    if (need[c]) {
+      info[c].residual = fn[c] > 0.0 ? std::sqrt(std::max(rn[c], 0.0)) / fn[c] : 0.0;
+      info[c].matvecs_fp64 += 1;
+    } else {
+      info[c].residual = res_known[c];
+    }
     info[c].seconds = sec;
   }
 }
