@@ -27,17 +27,19 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # Algorithmic flops per source-target pair of the far-field kernels, counted
-# from the source of the large-argument branch (z >= 2) that almost every pair
-# of this workload takes: an FMA counts 2, every other floating-point
-# arithmetic operation (add, mul, rsq, exp2, rint, ldexp) counts 1.
-#   FP32: 2 FP64 differences, r^2 (3), kappa^2 r^2 (1), rsq (1), z (1), rsq (1),
-#         exp2 argument + exp2 (2), s (1), degree-8 Horner (16), 3 products (3),
-#         (x-y).q (3), accumulate FMA (2)                                    = 36
-#   FP64: differences (2), r^2 (3), kappa^2 r^2 (1), two Newton-refined rsqrt
-#         (2 x 12), z (1), s (1), degree-20 Horner (40), e^-z by Cody-Waite +
-#         degree-13 Taylor (33), 3 products (3), (x-y).q (3), product (1),
-#         accumulate (1)                                                    = 113
-F_DL32 = 36
+# from the source: an FMA counts 2, every other floating-point arithmetic
+# operation (add, mul, rsq, exp2, rint, ldexp) counts 1.
+#   FP32, far path (every pair of a target group / source tile pair whose
+#         circles are at least 2 / kappa apart: 95 % of the pairs of this
+#         workload; the other 5 % take the general path, which costs more and is
+#         counted at this same figure): 2 differences, z^2 (3), rsq (1), Z (1),
+#         exp2 (1), rsq (1), degree-6 Horner (12), 3 products (3), D.q' (3),
+#         accumulate FMA (2)                                                   = 29
+#   FP64 (large-argument branch, which almost every pair takes): differences (2),
+#         r^2 (3), kappa^2 r^2 (1), two Newton-refined rsqrt (2 x 12), z (1), s (1),
+#         degree-20 Horner (40), e^-z by Cody-Waite + degree-13 Taylor (33),
+#         3 products (3), (x-y).q (3), product (1), accumulate (1)           = 113
+F_DL32 = 29
 F_DL64 = 113
 SRC_FOR_COUNTERS = ["paper_1810_04131_amd/csrc/farfield.hip",
                     "paper_1810_04131_amd/csrc/farfield_core.h", "paper_1810_04131_amd/csrc/bessel.h",

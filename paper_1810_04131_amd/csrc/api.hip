@@ -122,10 +122,10 @@ void apply_op(yq_problem* pb, const double* sigma, double* out, int prec) {
     return;
   }
   if (prec == YQ_MIXED) {
+    pb->pack32(sigma);
     {
       Timed t(pb, 1);
-      launch_far32(pb->x.p, pb->y.p, pb->wnx32.p, pb->wny32.p, sigma, pb->N, pb->kappa,
-                   pb->fp, pb->partial32.p, pb->stream);
+      launch_far32(pb->far32(), pb->fp, pb->partial32.p, pb->stream);
     }
     Timed t(pb, 2);
     launch_finish(g, win, pb->fp, nullptr, pb->partial32.p, pb->W.p, pb->xrow.p, pb->xpan.p,
@@ -500,11 +500,12 @@ int yq_set_particles(yq_problem* pb, int32_t n, const double* center_xy, const d
       launch_near_rows(g, pb->consts, pb->prm.near_oversample, pb->Lnear.p, pb->xrow.p,
                        pb->xpan.p, pb->xvals.p, pb->xgvals.p, s);
 
-    // FP32 copies for the mixed-precision far field
-    pb->wnx32.alloc(N);
-    pb->wny32.alloc(N);
-    launch_to_f32(pb->wnx.p, pb->wnx32.p, N, s);
-    launch_to_f32(pb->wny.p, pb->wny32.p, N, s);
+    // FP32 far field: bounding circles, relative positions, source records
+    pb->ftile.alloc((N + FT - 1) / FT);
+    pb->fgrp.alloc((N + FG - 1) / FG);
+    pb->frel.alloc(N);
+    pb->fsrc.alloc(N);
+    launch_far32_geom(pb->x.p, pb->y.p, N, kappa, pb->ftile.p, pb->fgrp.p, pb->frel.p, s);
 
     pb->fp = far_plan(N, N, 256, pb->far_want);
     pb->fmm.reset();
@@ -622,10 +623,10 @@ int yq_apply_far(yq_problem* pb, const double* sigma, double* out, int32_t preci
       return;
     }
     // far field with a zero near correction: reuse finish with window 0 rows skipped
-    if (precision == YQ_MIXED)
-      launch_far32(pb->x.p, pb->y.p, pb->wnx32.p, pb->wny32.p, sigma, pb->N, pb->kappa,
-                   pb->fp, pb->partial32.p, pb->stream);
-    else
+    if (precision == YQ_MIXED) {
+      pb->pack32(sigma);
+      launch_far32(pb->far32(), pb->fp, pb->partial32.p, pb->stream);
+    } else
       launch_far64(g, sigma, pb->fp, pb->partial.p, pb->stream);
     launch_finish(g, -1, pb->fp, precision == YQ_MIXED ? nullptr : pb->partial.p,
                   precision == YQ_MIXED ? pb->partial32.p : nullptr, pb->W.p, pb->xrow.p,

@@ -14,8 +14,8 @@ struct ConfDev {
   const double* y;
   const double* wnx;
   const double* wny;
-  const float* wnx32;
-  const float* wny32;
+  Far32View f32;          // FP32 far-field view (its src is the configuration's own records)
+  const float2* rel;      // scaled relative positions (pack input)
   const double* W;
   const int* xrow;
   const int* xpan;

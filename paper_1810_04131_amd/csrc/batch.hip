@@ -79,39 +79,39 @@ __global__ __launch_bounds__(BB) void bfar64_kernel(const ConfDev* __restrict__ 
   }
 }
 
+// Packs the FP32 source records of every active configuration.
+__global__ void bpack32_kernel(const ConfDev* __restrict__ cf, const int* __restrict__ node_conf,
+                               int64_t T, const int* __restrict__ mask,
+                               const double* __restrict__ V, const int* __restrict__ col) {
+  const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (g >= T) return;
+  const int c = node_conf[g];
+  if (c < 0 || !mask[c]) return;
+  const ConfDev& cd = cf[c];
+  const int64_t i = g - cd.off;
+  const double sc = V[(col ? (int64_t)col[c] * T : 0) + g] * cd.f32.qc;
+  const float2 r = cd.rel[i];
+  const_cast<float4*>(cd.f32.src)[i] =
+      make_float4(r.x, r.y, (float)(cd.wnx[i] * sc), (float)(cd.wny[i] * sc));
+}
+
+// Same arithmetic as far32_kernel for each (configuration, target block, source chunk).
 __global__ __launch_bounds__(BB) void bfar32_kernel(const ConfDev* __restrict__ cf,
                                                     const int4* __restrict__ items, int nitems,
-                                                    const int* __restrict__ mask,
-                                                    const double* __restrict__ V,
-                                                    const int* __restrict__ col, int64_t T) {
-  __shared__ double2 sxy[BB];
-  __shared__ float2 sq[BB];
+                                                    const int* __restrict__ mask) {
+  const int wib = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / FG));
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     const int4 w = items[it];
     const int c = w.x;
     if (!mask[c]) continue;
     const ConfDev& cd = cf[c];
     const int64_t N = cd.N;
-    const double* sg = V + (col ? (int64_t)col[c] * T : 0) + cd.off;
+    const int64_t g = (int64_t)w.y * (BB / FG) + wib;
+    if (g * FG >= N) continue;
     const int64_t i = (int64_t)w.y * BB + threadIdx.x;
-    const double xi = i < N ? cd.x[i] : 0.0;
-    const double yi = i < N ? cd.y[i] : 0.0;
     const int64_t j0 = (int64_t)w.z * cd.chunk;
     const int64_t j1 = min(N, j0 + cd.chunk);
-    float acc = 0.0f;
-    const float kap2 = (float)cd.kap2;
-    for (int64_t jb = j0; jb < j1; jb += BB) {
-      const int64_t j = jb + threadIdx.x;
-      __syncthreads();
-      if (j < j1) {
-        const float s = (float)sg[j];
-        sxy[threadIdx.x] = make_double2(cd.x[j], cd.y[j]);
-        sq[threadIdx.x] = make_float2(cd.wnx32[j] * s, cd.wny32[j] * s);
-      }
-      __syncthreads();
-      const int nb = (int)min((int64_t)BB, j1 - jb);
-      acc = far32_tile(xi, yi, sxy, sq, nb, kap2, acc);
-    }
+    const float acc = far32_range(cd.f32, i, g, j0, j1);
     if (i < N) cd.part32[(int64_t)w.z * N + i] = acc;
   }
 }
@@ -344,8 +344,8 @@ void Engine::rebuild() {
       d.y = pb->y.p;
       d.wnx = pb->wnx.p;
       d.wny = pb->wny.p;
-      d.wnx32 = pb->wnx32.p;
-      d.wny32 = pb->wny32.p;
+      d.f32 = pb->far32();
+      d.rel = pb->frel.p;
       d.W = pb->W.p;
       d.xrow = pb->xrow.p;
       d.xpan = pb->xpan.p;
@@ -438,9 +438,11 @@ int Engine::grid_blocks() const {
 // out = A sigma (precision prec) for configurations in mask; input column from V/col.
 void Engine::matvec(int prec, const int* mask, const double* Vin, const int* col, double* out) {
   if (nitems == 0) return;
-  if (prec == YQ_MIXED)
-    bfar32_kernel<<<grid_blocks(), BB, 0, stream>>>(conf.p, items.p, nitems, mask, Vin, col, T);
-  else
+  if (prec == YQ_MIXED) {
+    bpack32_kernel<<<nb256(T), 256, 0, stream>>>(conf.p, node_conf.p, T, mask, Vin, col);
+    YQ_HIP(hipGetLastError());
+    bfar32_kernel<<<grid_blocks(), BB, 0, stream>>>(conf.p, items.p, nitems, mask);
+  } else
     bfar64_kernel<<<grid_blocks(), BB, 0, stream>>>(conf.p, items.p, nitems, mask, Vin, col, T,
                                                     tab64.p);
   YQ_HIP(hipGetLastError());

@@ -167,17 +167,20 @@ __device__ inline void bessel_i_series64(double x, int lmax, double* I) {
 
 // ---- FP32 ------------------------------------------------------------------------------
 
+// K1(z)/z for z^2 = z2 (> 0, normal).  z < 2: the ascending series with the raw
+// base-2 logarithm (log2 t folded into the coefficients); z >= 2: e^-z z^-3/2
+// h1(2/z) with h1 as a degree-6 polynomial in 1/z.
 __device__ __forceinline__ float k1z_32(float z2) {
   if (z2 < 4.0f) {
-    float t = 0.25f * z2;
-    float lt = __logf(t);
-    return 0.25f * __builtin_amdgcn_rcpf(t) + 0.25f * (lt * horner(kE32, t) - horner(kF32, t));
+    const float t = 0.25f * z2;
+    const float l2 = __builtin_amdgcn_logf(t);
+    return fmaf(0.25f, __builtin_amdgcn_rcpf(t), fmaf(l2, horner(kE2_32, t), -horner(kF4_32, t)));
   }
-  float y = __builtin_amdgcn_rsqf(z2);
-  float z = z2 * y;
-  float q = __builtin_amdgcn_rsqf(z);
-  float e = __builtin_amdgcn_exp2f(-1.4426950408889634f * z);
-  return horner(kH1_32, 2.0f * y) * e * q * y;
+  const float y = __builtin_amdgcn_rsqf(z2);
+  const float z = z2 * y;
+  const float e = __builtin_amdgcn_exp2f(-1.4426950408889634f * z);
+  const float q = __builtin_amdgcn_rsqf(z);
+  return (e * horner(kH1Z_32, y)) * (q * y);
 }
 
 __device__ __forceinline__ void k0_k1z_32(float z2, float& k0, float& k1z) {

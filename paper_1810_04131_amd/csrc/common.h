@@ -123,7 +123,6 @@ void launch_geometry(const GeomView& g, const Consts& c, double* x, double* y, d
                      double* wnx, double* wny, hipStream_t s);
 void launch_panel_stats(const GeomView& g, double* panel_h, double* pcx, double* pcy, double* pr,
                         hipStream_t s);
-void launch_to_f32(const double* in, float* out, int64_t n, hipStream_t s);
 void launch_label(const GeomView& g, int kind, double a, double b, double* f, hipStream_t s);
 void launch_geom_check(const GeomView& g, const int* nb_ptr, const int* nb_idx, int* bad,
                        hipStream_t s);
@@ -143,11 +142,34 @@ struct FarPlan {
   int chunk;     // sources per chunk (multiple of the block size)
 };
 FarPlan far_plan(int64_t nt, int64_t ns, int block, int want = 4096);
+
+// FP32 far field (farfield_core.h): 256-node source tiles, 64-node target groups.
+constexpr int FT = 256;   // source tile (nodes)
+constexpr int FG = 64;    // target group (nodes)
+constexpr double LOG2E = 1.44269504088896340736;
+constexpr double SQRT_LOG2E = 1.20112240878644981;
+
+struct Far32View {
+  const double* x;     // FP64 node positions [N]
+  const double* y;
+  const double4* tile; // per 256-node tile: centre x, y, radius
+  const double4* grp;  // per 64-node group: centre x, y, radius
+  const float4* src;   // per node, packed per matvec
+  int64_t N;
+  double s;            // kappa log2(e)
+  double dfar;         // far when the gap between circles is >= 2 / kappa
+  double qc;           // sqrt(log2 e) / kappa: source strength scaling of the records
+  float kap2;          // kappa^2 (general path)
+  float nscale;        // kappa / sqrt(log2 e): general-path sum -> far-path scaling
+};
+
+void launch_far32_geom(const double* x, const double* y, int64_t N, double kappa, double4* tile,
+                       double4* grp, float2* rel, hipStream_t s);
+void launch_pack32(const float2* rel, const double* wnx, const double* wny, const double* sigma,
+                   int64_t N, double qc, float4* src, hipStream_t s);
 void launch_far64(const GeomView& g, const double* sigma, const FarPlan& fp, double* partial,
                   hipStream_t s);
-void launch_far32(const double* x, const double* y, const float* wnx, const float* wny,
-                  const double* sigma, int64_t N, double kappa, const FarPlan& fp, float* partial,
-                  hipStream_t s);
+void launch_far32(const Far32View& v, const FarPlan& fp, float* partial, hipStream_t s);
 void launch_finish(const GeomView& g, int win, const FarPlan& fp, const double* partial64,
                    const float* partial32, const double* W, const int* xrow, const int* xpan,
                    const double* xvals, const double* sigma, double* out, hipStream_t s);

@@ -62,39 +62,65 @@ __global__ __launch_bounds__(FAR_BS) void far64_kernel(GeomView g, const double*
   if (i < N) partial[(int64_t)blockIdx.y * N + i] = acc;
 }
 
-// FP32 far field.  Coordinates stay FP64: the difference x_i - y_j is formed
-// in FP64 and only then rounded to FP32, so adjacent nodes (r ~ 1e-2) in a box
-// of side ~100 keep a relative accuracy of ~1e-7 instead of ~1e-4.  The self
-// pair has r = 0 and (x_i - y_j).q_j = 0; clamping z^2 away from 0 keeps
-// K1(z)/z finite so that pair contributes exactly 0.
-__global__ __launch_bounds__(FAR_BS) void far32_kernel(const double* __restrict__ x,
-                                                       const double* __restrict__ y,
-                                                       const float* __restrict__ wnx,
-                                                       const float* __restrict__ wny,
-                                                       const double* __restrict__ sigma,
-                                                       int64_t N, float kap2, int chunk,
+// FP32 far field: one target per lane, one 64-target group per wavefront, a
+// block = 256 targets x one source chunk (grid.y).  No LDS and no barrier: the
+// sources reach every lane through scalar loads (far32_range).
+__global__ __launch_bounds__(FAR_BS) void far32_kernel(Far32View v, int chunk,
                                                        float* __restrict__ partial) {
-  __shared__ double2 sxy[FAR_BS];
-  __shared__ float2 sq[FAR_BS];
   const int64_t i = blockIdx.x * (int64_t)FAR_BS + threadIdx.x;
-  const double xi = i < N ? x[i] : 0.0;
-  const double yi = i < N ? y[i] : 0.0;
+  const int64_t g = blockIdx.x * (int64_t)(FAR_BS / FG) +
+                    __builtin_amdgcn_readfirstlane((int)(threadIdx.x / FG));
+  if (g * FG >= v.N) return;  // whole wavefront past the last node
   const int64_t j0 = (int64_t)blockIdx.y * chunk;
-  const int64_t j1 = min(N, j0 + chunk);
-  float acc = 0.0f;
-  for (int64_t jb = j0; jb < j1; jb += FAR_BS) {
-    const int64_t j = jb + threadIdx.x;
-    __syncthreads();
-    if (j < j1) {
-      const float s = (float)sigma[j];
-      sxy[threadIdx.x] = make_double2(x[j], y[j]);
-      sq[threadIdx.x] = make_float2(wnx[j] * s, wny[j] * s);
-    }
-    __syncthreads();
-    const int nb = (int)min((int64_t)FAR_BS, j1 - jb);
-    acc = far32_tile(xi, yi, sxy, sq, nb, kap2, acc);
+  const int64_t j1 = min(v.N, j0 + chunk);
+  const float acc = far32_range(v, i, g, j0, j1);
+  if (i < v.N) partial[(int64_t)blockIdx.y * v.N + i] = acc;
+}
+
+// Bounding circle of nodes [g G, min(N, g G + G)): centre of the bounding box,
+// radius = largest distance from it, enlarged by a relative 1e-12 so that
+// rounding cannot leave a node outside.
+__global__ void circles_kernel(const double* __restrict__ x, const double* __restrict__ y,
+                               int64_t N, int G, int64_t ng, double4* __restrict__ out) {
+  const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (g >= ng) return;
+  const int64_t a = g * G, b = min(N, a + G);
+  double x0 = x[a], x1 = x0, y0 = y[a], y1 = y0;
+  for (int64_t j = a + 1; j < b; ++j) {
+    x0 = fmin(x0, x[j]);
+    x1 = fmax(x1, x[j]);
+    y0 = fmin(y0, y[j]);
+    y1 = fmax(y1, y[j]);
   }
-  if (i < N) partial[(int64_t)blockIdx.y * N + i] = acc;
+  const double cx = 0.5 * (x0 + x1), cy = 0.5 * (y0 + y1);
+  double r2 = 0.0;
+  for (int64_t j = a; j < b; ++j) {
+    const double dx = x[j] - cx, dy = y[j] - cy;
+    r2 = fmax(r2, dx * dx + dy * dy);
+  }
+  const double r = sqrt(r2);
+  out[g] = make_double4(cx, cy, r + 1e-12 * (r + fabs(cx) + fabs(cy)), 0.0);
+}
+
+// Node positions relative to their tile centre, scaled by s = kappa log2(e).
+__global__ void rel32_kernel(const double* __restrict__ x, const double* __restrict__ y,
+                             int64_t N, const double4* __restrict__ tile, double s,
+                             float2* __restrict__ rel) {
+  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (j >= N) return;
+  const double4 t = tile[j / FT];
+  rel[j] = make_float2((float)((x[j] - t.x) * s), (float)((y[j] - t.y) * s));
+}
+
+// Per-matvec source records (rel x, rel y, q'x, q'y), q' = w nu sigma c.
+__global__ void pack32_kernel(const float2* __restrict__ rel, const double* __restrict__ wnx,
+                              const double* __restrict__ wny, const double* __restrict__ sigma,
+                              int64_t N, double c, float4* __restrict__ src) {
+  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (j >= N) return;
+  const double sc = sigma[j] * c;
+  const float2 r = rel[j];
+  src[j] = make_float4(r.x, r.y, (float)(wnx[j] * sc), (float)(wny[j] * sc));
 }
 
 // Gradient far field: grad_x of the double layer,
@@ -201,12 +227,26 @@ void launch_far64(const GeomView& g, const double* sigma, const FarPlan& fp, dou
   YQ_HIP(hipGetLastError());
 }
 
-void launch_far32(const double* x, const double* y, const float* wnx, const float* wny,
-                  const double* sigma, int64_t N, double kappa, const FarPlan& fp, float* partial,
-                  hipStream_t s) {
+void launch_far32_geom(const double* x, const double* y, int64_t N, double kappa, double4* tile,
+                       double4* grp, float2* rel, hipStream_t s) {
+  YQ_REQUIRE(N % Q == 0 && kappa > 0.0, YQ_EINVAL, "far32 geometry: N % 16 != 0 or kappa <= 0");
+  const int64_t nt = (N + FT - 1) / FT, ng = (N + FG - 1) / FG;
+  circles_kernel<<<(unsigned)((nt + 63) / 64), 64, 0, s>>>(x, y, N, FT, nt, tile);
+  circles_kernel<<<(unsigned)((ng + 63) / 64), 64, 0, s>>>(x, y, N, FG, ng, grp);
+  rel32_kernel<<<(unsigned)((N + 255) / 256), 256, 0, s>>>(x, y, N, tile, kappa * LOG2E, rel);
+  YQ_HIP(hipGetLastError());
+}
+
+void launch_pack32(const float2* rel, const double* wnx, const double* wny, const double* sigma,
+                   int64_t N, double qc, float4* src, hipStream_t s) {
+  pack32_kernel<<<(unsigned)((N + 255) / 256), 256, 0, s>>>(rel, wnx, wny, sigma, N, qc, src);
+  YQ_HIP(hipGetLastError());
+}
+
+void launch_far32(const Far32View& v, const FarPlan& fp, float* partial, hipStream_t s) {
+  YQ_REQUIRE(fp.chunk % FT == 0, YQ_EINVAL, "far32: chunk is not a multiple of the tile");
   dim3 grid(fp.tblocks, fp.chunks);
-  far32_kernel<<<grid, FAR_BS, 0, s>>>(x, y, wnx, wny, sigma, N, (float)(kappa * kappa), fp.chunk,
-                                       partial);
+  far32_kernel<<<grid, FAR_BS, 0, s>>>(v, fp.chunk, partial);
   YQ_HIP(hipGetLastError());
 }
 

@@ -23,7 +23,8 @@ __device__ __forceinline__ double far64_tile(double xi, double yi, const double2
   return acc;
 }
 
-// FP32 version; positions stay FP64 and the difference is rounded to FP32.
+// FP32 over an LDS-staged tile (FMM neighbour interactions); positions stay
+// FP64 and the difference is rounded to FP32.
 __device__ __forceinline__ float far32_tile(double xi, double yi, const double2* sxy,
                                            const float2* sq, int nb, float kap2, float acc) {
   for (int k = 0; k < nb; ++k) {
@@ -34,6 +35,110 @@ __device__ __forceinline__ float far32_tile(double xi, double yi, const double2*
     acc = fmaf(k1z_32(z2), fmaf(dx, q.x, dy * q.y), acc);
   }
   return acc;
+}
+
+// ---- FP32 far field ----------------------------------------------------------------------
+//
+// Sources are visited in tiles of 256 consecutive nodes, targets in groups of
+// 64 (one wavefront); each has a bounding circle computed once per geometry.
+// A (group, tile) pair is "far" when kappa times the gap between the circles is
+// at least 2, so every pair in it has z >= 2: those pairs take a branch-free
+// path in coordinates scaled by kappa log2(e) and taken relative to the tile
+// centre (no FP64 arithmetic per pair).  Other pairs take the general path:
+// FP64 differences rounded to FP32 (adjacent nodes stay accurate) and both
+// branches of K1(z)/z.  Sources are packed per matvec into
+// (rel x, rel y, q'x, q'y), q' = w nu sigma sqrt(log2 e) / kappa, and read
+// through scalar loads: every lane of a wavefront needs the same source.
+
+// Uniform loads through a constant-address-space pointer become scalar loads.
+template <class T>
+using kptr = const __attribute__((address_space(4))) T*;
+template <class T>
+__device__ __forceinline__ kptr<T> as_k(const T* p) {
+  return (kptr<T>)p;
+}
+
+
+// Far pairs: with D = s (x_i - y_j), Z2 = |D|^2 = (z log2 e)^2, Y = 1/sqrt(Z2),
+// K1(z)/z ((x_i - y_j) . q) = 2^-Z h1(2 log2(e) Y) (Y / sqrt(Z)) (D . q').
+__device__ __forceinline__ float far32_pair(float tx, float ty, float4 p, float acc) {
+  const float dx = tx - p.x, dy = ty - p.y;
+  const float z2 = fmaf(dx, dx, dy * dy);
+  const float yv = __builtin_amdgcn_rsqf(z2);
+  const float z = z2 * yv;
+  const float e = __builtin_amdgcn_exp2f(-z);
+  const float q = __builtin_amdgcn_rsqf(z);
+  const float h = horner(kH1Y_32, yv);
+  return fmaf((e * h) * (q * yv), fmaf(dx, p.z, dy * p.w), acc);
+}
+
+__device__ __forceinline__ float4 ld_rec(kptr<float> p) {
+  return make_float4(p[0], p[1], p[2], p[3]);
+}
+
+// sp: the tile's records as 4 floats each; nb a multiple of 16 (panels hold 16
+// nodes).  The next 4 records are loaded (scalar) before the current 4 are used.
+__device__ __forceinline__ float far32_far_tile(float tx, float ty, kptr<float> sp, int nb,
+                                                float acc) {
+  float4 a0 = ld_rec(sp), a1 = ld_rec(sp + 4), a2 = ld_rec(sp + 8), a3 = ld_rec(sp + 12);
+  for (int k = 0; k < nb; k += 4) {
+    kptr<float> pn = sp + 4 * (k + 4 < nb ? k + 4 : k);
+    const float4 b0 = ld_rec(pn), b1 = ld_rec(pn + 4), b2 = ld_rec(pn + 8), b3 = ld_rec(pn + 12);
+    acc = far32_pair(tx, ty, a0, acc);
+    acc = far32_pair(tx, ty, a1, acc);
+    acc = far32_pair(tx, ty, a2, acc);
+    acc = far32_pair(tx, ty, a3, acc);
+    a0 = b0;
+    a1 = b1;
+    a2 = b2;
+    a3 = b3;
+  }
+  return acc;
+}
+
+// General pairs (any z, including the self pair, whose z^2 is clamped away from
+// 0 while (x_i - y_j) . q = 0).  Sums K1(z)/z ((x_i - y_j) . q') with unscaled
+// differences.
+__device__ __forceinline__ float far32_near_tile(double xi, double yi, kptr<double> sx,
+                                                 kptr<double> sy, kptr<float> sp, int nb,
+                                                 float kap2, float acc) {
+  for (int k = 0; k < nb; k += 4) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      kptr<float> p = sp + 4 * (k + u);
+      const float dx = (float)(xi - sx[k + u]), dy = (float)(yi - sy[k + u]);
+      const float z2 = fmaxf(kap2 * fmaf(dx, dx, dy * dy), 1e-30f);
+      acc = fmaf(k1z_32(z2), fmaf(dx, p[2], dy * p[3]), acc);
+    }
+  }
+  return acc;
+}
+
+// Sum over sources [j0, j1) (j0 a multiple of 256, j1 - j0 a multiple of 16) for
+// target i of target group g (wavefront-uniform), in the scaling of far64_tile.
+__device__ __forceinline__ float far32_range(const Far32View& v, int64_t i, int64_t g,
+                                             int64_t j0, int64_t j1) {
+  const double xi = i < v.N ? v.x[i] : 0.0;
+  const double yi = i < v.N ? v.y[i] : 0.0;
+  kptr<double> gc = as_k((const double*)v.grp) + 4 * g;
+  const double gx = gc[0], gy = gc[1], gr = gc[2];
+  kptr<float> src = as_k((const float*)v.src);
+  float accf = 0.0f, accn = 0.0f;
+  for (int64_t jb = j0; jb < j1; jb += FT) {
+    kptr<double> tc = as_k((const double*)v.tile) + 4 * (jb / FT);
+    const double tcx = tc[0], tcy = tc[1];
+    const double cx = gx - tcx, cy = gy - tcy;
+    const double gap = sqrt(cx * cx + cy * cy) - gr - tc[2];
+    const int nb = (int)min((int64_t)FT, j1 - jb);
+    if (gap >= v.dfar) {
+      const float tx = (float)((xi - tcx) * v.s), ty = (float)((yi - tcy) * v.s);
+      accf = far32_far_tile(tx, ty, src + 4 * jb, nb, accf);
+    } else {
+      accn = far32_near_tile(xi, yi, as_k(v.x) + jb, as_k(v.y) + jb, src + 4 * jb, nb, v.kap2,
+                             accn);
+    }
+  }
+  return fmaf(accn, v.nscale, accf);
 }
 
 // Gradient of the double layer over a staged source tile, accumulated into

@@ -139,11 +139,6 @@ __global__ void panel_stats_kernel(GeomView g, double* __restrict__ h, double* _
   pr[J] = sqrt(r2) * (1.0 + 1e-12) + 1e-300;
 }
 
-__global__ void to_f32_kernel(const double* __restrict__ in, float* __restrict__ out, int64_t n) {
-  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i < n) out[i] = (float)in[i];
-}
-
 __global__ void label_kernel(GeomView g, int kind, double a, double b, double* __restrict__ f) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= g.N) return;
@@ -243,12 +238,6 @@ void launch_geometry(const GeomView& g, const Consts& c, double* x, double* y, d
 void launch_panel_stats(const GeomView& g, double* panel_h, double* pcx, double* pcy, double* pr,
                         hipStream_t s) {
   panel_stats_kernel<<<nblk((int64_t)g.n * g.P, 256), 256, 0, s>>>(g, panel_h, pcx, pcy, pr);
-  YQ_HIP(hipGetLastError());
-}
-
-void launch_to_f32(const double* in, float* out, int64_t n, hipStream_t s) {
-  if (n == 0) return;
-  to_f32_kernel<<<nblk(n, 256), 256, 0, s>>>(in, out, n);
   YQ_HIP(hipGetLastError());
 }
 

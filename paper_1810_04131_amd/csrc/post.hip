@@ -158,7 +158,8 @@ __global__ void bessel_kernel(int kind, int order, int prec, int64_t n, const do
     float k0, k1z;
     float xf = (float)x;
     k0_k1z_32(xf * xf, k0, k1z);
-    v = kind == 0 ? (double)k0 : (double)(k1z * xf);
+    // K1 through k1z_32, the evaluation of the FP32 pair kernels
+    v = kind == 0 ? (double)k0 : (double)(k1z_32(xf * xf) * xf);
   } else if (kind == 0 || kind == 1 || kind == 2) {
     double k0, k1;
     k01_64(x, k0, k1, tab);

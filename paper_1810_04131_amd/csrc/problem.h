@@ -23,11 +23,15 @@ struct yq_problem {
   bool batch_member = false;  // workspace for GMRES/forces comes from the batch
   std::unique_ptr<Fmm> fmm;     // far-field FMM (inner operator) when enabled
   std::unique_ptr<Fmm> fmm_hi;  // higher-order FP64 FMM for residuals (fmm_resid_order > 0)
-  int far_want = 4096;        // far-field plan parameter (far_plan)
+  int far_want = 8192;        // far-field plan parameter (far_plan)
 
   std::vector<double> h_pc;  // [n*5]
   DevBuf<double> pc, x, y, nx, ny, w, wnx, wny, panel_h, pcx, pcy, pr;
-  DevBuf<float> wnx32, wny32;
+  // FP32 far field: tile / group bounding circles, scaled relative positions,
+  // per-matvec packed sources
+  DevBuf<double4> ftile, fgrp;
+  DevBuf<float2> frel;
+  DevBuf<float4> fsrc;
   DevBuf<double> pot_partial;
   DevBuf<int> nb_ptr, nb_idx, bad;
   DevBuf<int> xrow, xpan;
@@ -67,6 +71,27 @@ struct yq_problem {
         (void)hipEventDestroy(p.second);
       }
     for (auto e : pool) (void)hipEventDestroy(e);
+  }
+
+  Far32View far32() const {
+    Far32View v;
+    v.x = x.p;
+    v.y = y.p;
+    v.tile = ftile.p;
+    v.grp = fgrp.p;
+    v.src = fsrc.p;
+    v.N = N;
+    v.s = kappa * LOG2E;
+    v.dfar = 2.0 / kappa;
+    v.qc = SQRT_LOG2E / kappa;   // the same expression as in pack32
+    v.kap2 = (float)(kappa * kappa);
+    v.nscale = (float)(kappa / SQRT_LOG2E);
+    return v;
+  }
+
+  // packs sigma into the FP32 source records (before every FP32 far field)
+  void pack32(const double* sigma) {
+    launch_pack32(frel.p, wnx.p, wny.p, sigma, N, SQRT_LOG2E / kappa, fsrc.p, stream);
   }
 
   GeomView view() const {

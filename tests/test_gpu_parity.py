@@ -126,6 +126,22 @@ def test_far_field_parity(small):
     assert _rel(got32, ref) < 5e-6
 
 
+@pytest.mark.parametrize("kappa", [0.5, 1.0, 2.0])
+def test_far32_tile_paths_parity(kappa):
+    """FP32 far field where most (target group, source tile) pairs take the far
+    path (kappa x gap >= 2: scaled relative coordinates, large-argument branch
+    only) and the rest the general path; N = 4368 is ragged in both the 64-node
+    groups and the 256-node tiles."""
+    parts = workloads.random_ellipses(13, 16.0, kappa, seed=3)
+    pb = _problem(parts, 21, 6)
+    d = oracle.discretize(parts, _oprm(21, 6))
+    assert pb.N == d.N == 4368
+    sig = workloads.random_density(d.N, 17)
+    ref = oracle.far_rows(d, list(range(d.N)), sig)
+    got32 = _np(pb.apply_far(sig, precision=yq.YQ_MIXED))
+    assert _rel(got32, ref) < 5e-6
+
+
 def test_operator_parity(small):
     pb = _problem(small["parts"], small["P"], small["p"])
     d = small["d"]
