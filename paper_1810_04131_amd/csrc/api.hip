@@ -84,12 +84,12 @@ void check_params(const yq_params& p) {
 }
 
 void upload(DevBuf<double>& b, const std::vector<double>& h, hipStream_t s) {
-  b.alloc(h.size());
+  b.fit(h.size());
   YQ_HIP(hipMemcpyAsync(b.p, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice, s));
 }
 
 void upload_i(DevBuf<int>& b, const std::vector<int>& h, hipStream_t s) {
-  b.alloc(std::max<size_t>(h.size(), 1));
+  b.fit(std::max<size_t>(h.size(), 1));
   if (!h.empty())
     YQ_HIP(hipMemcpyAsync(b.p, h.data(), h.size() * sizeof(int), hipMemcpyHostToDevice, s));
 }
@@ -423,15 +423,53 @@ int yq_set_particles(yq_problem* pb, int32_t n, const double* center_xy, const d
     // a near panel of, or overlap, particle p; p itself is included.
     const double margin = std::max(pb->prm.near_beta, pb->prm.pot_beta) * 2.0 * PI * amax / P *
                               1.01 + 1e-9;
+    // Candidates come from a uniform grid of cell side 2 amax + margin (no pair
+    // closer than that can be missed); each list is ascending in q.
     std::vector<int> nbp(n + 1, 0), nbi;
-    for (int p = 0; p < n; ++p) {
-      const double* a = &pb->h_pc[5 * (size_t)p];
-      for (int q = 0; q < n; ++q) {
-        const double* b = &pb->h_pc[5 * (size_t)q];
-        const double d = std::hypot(a[0] - b[0], a[1] - b[1]);
-        if (q == p || d < a[3] + b[3] + margin) nbi.push_back(q);
+    {
+      double xlo = pb->h_pc[0], ylo = pb->h_pc[1], xhi = xlo, yhi = ylo;
+      for (int p = 0; p < n; ++p) {
+        xlo = std::min(xlo, pb->h_pc[5 * (size_t)p]);
+        xhi = std::max(xhi, pb->h_pc[5 * (size_t)p]);
+        ylo = std::min(ylo, pb->h_pc[5 * (size_t)p + 1]);
+        yhi = std::max(yhi, pb->h_pc[5 * (size_t)p + 1]);
       }
-      nbp[p + 1] = (int)nbi.size();
+      // at most 1024 cells per side (larger cells only add candidates)
+      const double cell = std::max(2.0 * amax + margin, std::max(xhi - xlo, yhi - ylo) / 1024.0);
+      const int64_t gx = std::min<int64_t>((int64_t)((xhi - xlo) / cell) + 1, 1025);
+      const int64_t gy = std::min<int64_t>((int64_t)((yhi - ylo) / cell) + 1, 1025);
+      auto cell_of = [&](double v, double lo, int64_t g) {
+        return std::min<int64_t>(std::max<int64_t>((int64_t)((v - lo) / cell), 0), g - 1);
+      };
+      std::vector<int> head(gx * gy + 1, 0), members(n);
+      std::vector<int64_t> cid(n);
+      for (int p = 0; p < n; ++p) {
+        cid[p] = cell_of(pb->h_pc[5 * (size_t)p], xlo, gx) * gy +
+                 cell_of(pb->h_pc[5 * (size_t)p + 1], ylo, gy);
+        ++head[cid[p] + 1];
+      }
+      for (int64_t c = 0; c < gx * gy; ++c) head[c + 1] += head[c];
+      {
+        std::vector<int> fill(head.begin(), head.end() - 1);
+        for (int p = 0; p < n; ++p) members[fill[cid[p]]++] = p;
+      }
+      std::vector<int> cand;
+      for (int p = 0; p < n; ++p) {
+        const double* a = &pb->h_pc[5 * (size_t)p];
+        const int64_t cx = cid[p] / gy, cy = cid[p] % gy;
+        cand.clear();
+        for (int64_t ix = std::max<int64_t>(cx - 1, 0); ix <= std::min(cx + 1, gx - 1); ++ix)
+          for (int64_t iy = std::max<int64_t>(cy - 1, 0); iy <= std::min(cy + 1, gy - 1); ++iy)
+            for (int e = head[ix * gy + iy]; e < head[ix * gy + iy + 1]; ++e) {
+              const int q = members[e];
+              const double* b = &pb->h_pc[5 * (size_t)q];
+              const double d = std::hypot(a[0] - b[0], a[1] - b[1]);
+              if (q == p || d < a[3] + b[3] + margin) cand.push_back(q);
+            }
+        std::sort(cand.begin(), cand.end());
+        nbi.insert(nbi.end(), cand.begin(), cand.end());
+        nbp[p + 1] = (int)nbi.size();
+      }
     }
     upload(pb->pc, pb->h_pc, s);
     upload_i(pb->nb_ptr, nbp, s);
@@ -463,10 +501,22 @@ int yq_set_particles(yq_problem* pb, int32_t n, const double* center_xy, const d
     YQ_HIP(hipStreamSynchronize(s));
     YQ_REQUIRE(bad == 0, YQ_EGEOM, "a node of one particle lies inside another particle");
 
+    // the FMM tree is built on the host from the node positions; their copy is
+    // queued now so that the QBX build below runs while the tree is built
+    const bool use_fmm = !pb->batch_member &&
+                         (pb->prm.far_mode == YQ_FAR_FMM ||
+                          (pb->prm.far_mode == YQ_FAR_AUTO && N >= kFmmAutoNodes));
+    if (use_fmm) {
+      // the FMM objects of the previous geometry are rebuilt in place: their
+      // device buffers only grow, so a new geometry frees nothing
+      if (!pb->fmm) pb->fmm = std::make_unique<Fmm>();
+      pb->fmm->download(pb->x.p, pb->y.p, pb->wnx.p, pb->wny.p, N, s);
+    }
+
     // a3: extra near panels (count, prefix sum, fill)
     pb->xrow.alloc(N + 1);
-    DevBuf<int> cnt;
-    cnt.alloc(N);
+    DevBuf<int>& cnt = pb->ncnt;
+    cnt.fit(N);
     launch_near_count(g, pb->prm.qbx_window, pb->prm.near_beta, pb->nb_ptr.p, pb->nb_idx.p,
                       pb->pcx.p, pb->pcy.p, pb->pr.p, cnt.p, nullptr, nullptr, s);
     std::vector<int> hc(N), hrow(N + 1, 0);
@@ -475,9 +525,9 @@ int yq_set_particles(yq_problem* pb, int32_t n, const double* center_xy, const d
     for (int64_t i = 0; i < N; ++i) hrow[i + 1] = hrow[i] + hc[i];
     pb->x_total = hrow[N];
     YQ_HIP(hipMemcpyAsync(pb->xrow.p, hrow.data(), (N + 1) * sizeof(int), hipMemcpyHostToDevice, s));
-    pb->xpan.alloc(std::max<int64_t>(pb->x_total, 1));
-    pb->xvals.alloc(std::max<int64_t>(pb->x_total, 1) * Q);
-    pb->xgvals.alloc(std::max<int64_t>(pb->x_total, 1) * 2 * Q);
+    pb->xpan.fit(std::max<int64_t>(pb->x_total, 1));
+    pb->xvals.fit(std::max<int64_t>(pb->x_total, 1) * Q);
+    pb->xgvals.fit(std::max<int64_t>(pb->x_total, 1) * 2 * Q);
     if (pb->x_total > 0)
       launch_near_count(g, pb->prm.qbx_window, pb->prm.near_beta, pb->nb_ptr.p, pb->nb_idx.p,
                         pb->pcx.p, pb->pcy.p, pb->pr.p, nullptr, pb->xpan.p, pb->xrow.p, s);
@@ -508,20 +558,19 @@ int yq_set_particles(yq_problem* pb, int32_t n, const double* center_xy, const d
     launch_far32_geom(pb->x.p, pb->y.p, N, kappa, pb->ftile.p, pb->fgrp.p, pb->frel.p, s);
 
     pb->fp = far_plan(N, N, 256, pb->far_want);
-    pb->fmm.reset();
-    pb->fmm_hi.reset();
-    const bool use_fmm = pb->prm.far_mode == YQ_FAR_FMM ||
-                         (pb->prm.far_mode == YQ_FAR_AUTO && N >= kFmmAutoNodes);
-    if (use_fmm && !pb->batch_member) {
-      pb->fmm = std::make_unique<Fmm>();
+    if (use_fmm) {
       pb->fmm->use_mfma = pb->prm.fmm_m2l == YQ_M2L_MFMA;
-      pb->fmm->build(pb->x.p, pb->y.p, pb->wnx.p, pb->wny.p, N, kappa, pb->prm.fmm_order,
-                     pb->prm.fmm_leaf_max, pb->tab.p, s);
+      pb->fmm->build(N, kappa, pb->prm.fmm_order, pb->prm.fmm_leaf_max, pb->tab.p, s);
       if (pb->prm.fmm_resid_order > 0) {
-        pb->fmm_hi = std::make_unique<Fmm>();
+        if (!pb->fmm_hi) pb->fmm_hi = std::make_unique<Fmm>();
         pb->fmm_hi->use_mfma = pb->prm.fmm_m2l == YQ_M2L_MFMA;
         pb->fmm_hi->copy_tree(*pb->fmm, pb->prm.fmm_resid_order, pb->tab.p, s);
+      } else {
+        pb->fmm_hi.reset();
       }
+    } else {
+      pb->fmm.reset();
+      pb->fmm_hi.reset();
     }
     pb->partial.alloc((size_t)pb->fp.chunks * N);
     pb->partial32.alloc((size_t)pb->fp.chunks * N);
@@ -668,8 +717,8 @@ int yq_solve(yq_problem* pb, const double* sigma0, double* sigma, yq_solve_info*
     } else {
       // mixed precision: FP64 residual, FP32-far-field inner GMRES, sigma += delta
       if (zero) YQ_HIP(hipMemsetAsync(sigma, 0, N * sizeof(double), s));
-      DevBuf<double> delta;
-      delta.alloc(N);
+      DevBuf<double>& delta = pb->delta;
+      delta.fit(N);
       const double fnorm = std::sqrt(dot_host(pb, pb->f.p, pb->f.p));
       int budget = pb->prm.maxiter;
       for (int outer = 0; outer < pb->prm.max_refine; ++outer) {

@@ -39,25 +39,30 @@ struct Error {
     if (!(cond)) throw ::yq::Error{(code), (msg)};                                         \
   } while (0)
 
-// Owning device buffer (hipMalloc / hipFree).
+// Owning device buffer (hipMalloc / hipFree).  alloc() gives exactly the
+// requested size; fit() only grows (the logical size n may be below the
+// capacity), so buffers rebuilt for every geometry stop calling hipFree, which
+// waits for the device.
 template <class T>
 struct DevBuf {
   T* p = nullptr;
   size_t n = 0;
+  size_t cap = 0;
   DevBuf() = default;
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
-  DevBuf(DevBuf&& o) noexcept : p(o.p), n(o.n) {
+  DevBuf(DevBuf&& o) noexcept : p(o.p), n(o.n), cap(o.cap) {
     o.p = nullptr;
-    o.n = 0;
+    o.n = o.cap = 0;
   }
   DevBuf& operator=(DevBuf&& o) noexcept {
     if (this != &o) {
       release();
       p = o.p;
       n = o.n;
+      cap = o.cap;
       o.p = nullptr;
-      o.n = 0;
+      o.n = o.cap = 0;
     }
     return *this;
   }
@@ -65,7 +70,7 @@ struct DevBuf {
   void release() {
     if (p) (void)hipFree(p);
     p = nullptr;
-    n = 0;
+    n = cap = 0;
   }
   void alloc(size_t count) {
     if (count == n && p) return;
@@ -77,13 +82,46 @@ struct DevBuf {
       throw Error{YQ_ENOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) +
                                  " bytes failed: " + hipGetErrorString(e)};
     }
-    n = count;
+    n = cap = count;
   }
-  // grows, never shrinks
+  // grows, never shrinks; n = count
+  void fit(size_t count) {
+    if (p && count <= cap) {
+      n = count;
+      return;
+    }
+    alloc(count);
+  }
+  // grows, never shrinks (n becomes the new capacity)
   void reserve(size_t count) {
     if (count > n) alloc(count);
   }
   size_t bytes() const { return n * sizeof(T); }
+};
+
+// Grow-only pinned host buffer (hipHostMalloc), for staging set-up transfers.
+struct PinnedBuf {
+  char* p = nullptr;
+  size_t cap = 0;
+  PinnedBuf() = default;
+  PinnedBuf(const PinnedBuf&) = delete;
+  PinnedBuf& operator=(const PinnedBuf&) = delete;
+  ~PinnedBuf() {
+    if (p) (void)hipHostFree(p);
+  }
+  void fit(size_t bytes) {
+    if (p && bytes <= cap) return;
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    cap = 0;
+    hipError_t e = hipHostMalloc((void**)&p, bytes, hipHostMallocDefault);
+    if (e != hipSuccess) {
+      p = nullptr;
+      throw Error{YQ_ENOMEM, "hipHostMalloc of " + std::to_string(bytes) + " bytes failed: " +
+                                 hipGetErrorString(e)};
+    }
+    cap = bytes;
+  }
 };
 
 // Geometry of one problem as the kernels see it (all device pointers).

@@ -41,9 +41,25 @@ struct Fmm {
   DevBuf<double> gmat;    // M2M / L2L matrices [level][child position][R16 * R16], same order
   DevBuf<int2> m2l_tiles; // (level, first box) of every 16-box M2L tile
   int n_m2l_tiles = 0;
+  PinnedBuf stage_up, stage_dn;   // set-up transfers (grow-only, reused by every build)
+  DevBuf<double> bbox;            // node bounding box (xmin, xmax, ymin, ymax)
+  DevBuf<uint32_t> keys, skeys;   // finest-level Morton keys, unsorted / sorted
+  DevBuf<int> iota;               // 0..N-1 (sort payload)
+  DevBuf<char> sort_tmp;          // radix-sort scratch
 
-  void build(const double* dx, const double* dy, const double* dwnx, const double* dwny,
-             int64_t n, double kappa, int order, int leaf_max, const double* tab, hipStream_t s);
+  hipEvent_t dn_done = nullptr;   // recorded after download()
+
+  Fmm() = default;
+  Fmm(const Fmm&) = delete;
+  Fmm& operator=(const Fmm&) = delete;
+  ~Fmm();
+  // Queues the device part of the tree build (bounding box, Morton keys, their
+  // stable sort, the sorted copies of positions and w nu) and the copy of the
+  // sorted keys to the host; build() waits for that copy, so kernels queued in
+  // between run while the host builds the levels and lists.
+  void download(const double* dx, const double* dy, const double* dwnx, const double* dwny,
+                int64_t n, hipStream_t s);
+  void build(int64_t n, double kappa, int order, int leaf_max, const double* tab, hipStream_t s);
   void set_order(int q, const double* tab, hipStream_t s);
   void copy_tree(const Fmm& o, int q, const double* tab, hipStream_t s);
   // partial[i] = (2 pi / kappa^2) * far field at node i (the far-field kernels' scaling)

@@ -24,10 +24,13 @@
 // device.
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <memory>
 #include <numeric>
 #include <type_traits>
 #include <unordered_map>
+
+#include <hipcub/hipcub.hpp>
 
 #include "bessel.h"
 #include "common.h"
@@ -625,6 +628,87 @@ __global__ __launch_bounds__(FB) void l2p_p2p_grad_kernel(int p, double kappa,
   }
 }
 
+// ---- tree keys (device) ------------------------------------------------------------------
+
+// Bounding box of the nodes, out = (xmin, xmax, ymin, ymax); one block (min and
+// max are exact, so the order of the reduction does not matter).
+constexpr int BBOX_BS = 1024;
+__global__ __launch_bounds__(BBOX_BS) void bbox_kernel(const double* __restrict__ x,
+                                                       const double* __restrict__ y, int64_t n,
+                                                       double* __restrict__ out) {
+  __shared__ double sh[4][BBOX_BS];
+  double a = x[0], b = x[0], c = y[0], d = y[0];
+  for (int64_t i = threadIdx.x; i < n; i += BBOX_BS) {
+    a = fmin(a, x[i]);
+    b = fmax(b, x[i]);
+    c = fmin(c, y[i]);
+    d = fmax(d, y[i]);
+  }
+  sh[0][threadIdx.x] = a;
+  sh[1][threadIdx.x] = b;
+  sh[2][threadIdx.x] = c;
+  sh[3][threadIdx.x] = d;
+  __syncthreads();
+  for (int o = BBOX_BS / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      sh[0][threadIdx.x] = fmin(sh[0][threadIdx.x], sh[0][threadIdx.x + o]);
+      sh[1][threadIdx.x] = fmax(sh[1][threadIdx.x], sh[1][threadIdx.x + o]);
+      sh[2][threadIdx.x] = fmin(sh[2][threadIdx.x], sh[2][threadIdx.x + o]);
+      sh[3][threadIdx.x] = fmax(sh[3][threadIdx.x], sh[3][threadIdx.x + o]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < 4) out[threadIdx.x] = sh[threadIdx.x][0];
+}
+
+// The root box: side W and lower-left corner (x0, y0), from the bounding box.
+__host__ __device__ inline void root_box(const double* bb, double& W, double& x0, double& y0) {
+  W = fmax(bb[1] - bb[0], bb[3] - bb[2]) * (1.0 + 1e-9) + 1e-12;
+  x0 = 0.5 * (bb[0] + bb[1]) - 0.5 * W;
+  y0 = 0.5 * (bb[2] + bb[3]) - 0.5 * W;
+}
+
+__device__ __forceinline__ uint32_t spread16(uint32_t v) {
+  v &= 0xffffu;
+  v = (v | (v << 8)) & 0x00ff00ffu;
+  v = (v | (v << 4)) & 0x0f0f0f0fu;
+  v = (v | (v << 2)) & 0x33333333u;
+  v = (v | (v << 1)) & 0x55555555u;
+  return v;
+}
+
+// Morton key of every node on the 2^DMAX x 2^DMAX grid of the root box (x in
+// the even bits), and the sort payload i.
+__global__ void keys_kernel(const double* __restrict__ x, const double* __restrict__ y, int64_t n,
+                            const double* __restrict__ bb, int dmax, uint32_t* __restrict__ key,
+                            int* __restrict__ iota) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double W, x0, y0;
+  root_box(bb, W, x0, y0);
+  const int64_t m = 1LL << dmax;
+  int64_t ix = (int64_t)((x[i] - x0) / W * m), iy = (int64_t)((y[i] - y0) / W * m);
+  ix = min(max(ix, (int64_t)0), m - 1);
+  iy = min(max(iy, (int64_t)0), m - 1);
+  key[i] = spread16((uint32_t)ix) | (spread16((uint32_t)iy) << 1);
+  iota[i] = (int)i;
+}
+
+// Sorted copies of positions and w nu (perm: sorted position -> node).
+__global__ void sort_gather_kernel(int64_t n, const int* __restrict__ perm,
+                                   const double* __restrict__ x, const double* __restrict__ y,
+                                   const double* __restrict__ wx, const double* __restrict__ wy,
+                                   double* __restrict__ xs, double* __restrict__ ys,
+                                   double* __restrict__ wxs, double* __restrict__ wys) {
+  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const int i = perm[k];
+  xs[k] = x[i];
+  ys[k] = y[i];
+  wxs[k] = wx[i];
+  wys[k] = wy[i];
+}
+
 // ---- host --------------------------------------------------------------------------------
 
 // Bit interleaving for Morton keys (x in the even bits), grid coordinates < 2^31.
@@ -654,42 +738,43 @@ static inline void unmorton(int64_t k, int64_t& ix, int64_t& iy) {
   iy = (int64_t)gather_bits((uint64_t)k >> 1);
 }
 
-// Stable LSD radix sort of n (key, index) pairs packed as key << 32 | index,
-// keys below 2^kbits.
-static void radix_sort_keys(std::vector<uint64_t>& a, int kbits) {
-  std::vector<uint64_t> b(a.size());
-  constexpr int D = 11;
-  for (int sh = 32; sh < 32 + kbits; sh += D) {
-    std::vector<size_t> cnt((1 << D) + 1, 0);
-    for (uint64_t v : a) ++cnt[((v >> sh) & ((1 << D) - 1)) + 1];
-    for (int d = 0; d < (1 << D); ++d) cnt[d + 1] += cnt[d];
-    for (uint64_t v : a) b[cnt[(v >> sh) & ((1 << D) - 1)]++] = v;
-    a.swap(b);
-  }
-}
-
-// Host-to-device uploads during set-up: asynchronous, each from a copy held
-// until finish() (or destruction) waits for the stream.
+// Host-to-device uploads during set-up: each array is kept until finish(), which
+// packs them into the pinned staging buffer, issues one asynchronous copy per
+// array and waits for the stream.  Device buffers only grow (DevBuf::fit).
 struct Uploader {
   hipStream_t s;
-  std::vector<std::shared_ptr<void>> keep;
-  explicit Uploader(hipStream_t st) : s(st) {}
+  PinnedBuf& stage;
+  struct Item {
+    void* dst;
+    std::shared_ptr<void> keep;
+    const void* src;
+    size_t bytes;
+  };
+  std::vector<Item> items;
+  Uploader(hipStream_t st, PinnedBuf& sb) : s(st), stage(sb) {}
   Uploader(const Uploader&) = delete;
   Uploader& operator=(const Uploader&) = delete;
-  ~Uploader() {
-    if (!keep.empty()) (void)hipStreamSynchronize(s);
-  }
   template <class T>
   void operator()(DevBuf<T>& d, const std::vector<T>& h) {
-    d.alloc(std::max<size_t>(h.size(), 1));
+    d.fit(std::max<size_t>(h.size(), 1));
     if (h.empty()) return;
     auto c = std::make_shared<std::vector<T>>(h);
-    YQ_HIP(hipMemcpyAsync(d.p, c->data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
-    keep.push_back(std::move(c));
+    items.push_back({d.p, c, c->data(), h.size() * sizeof(T)});
   }
   void finish() {
+    size_t total = 0;
+    for (const Item& it : items) total += (it.bytes + 255) & ~(size_t)255;
+    if (total) {
+      stage.fit(total);
+      size_t off = 0;
+      for (const Item& it : items) {
+        std::memcpy(stage.p + off, it.src, it.bytes);
+        YQ_HIP(hipMemcpyAsync(it.dst, stage.p + off, it.bytes, hipMemcpyHostToDevice, s));
+        off += (it.bytes + 255) & ~(size_t)255;
+      }
+    }
     YQ_HIP(hipStreamSynchronize(s));
-    keep.clear();
+    items.clear();
   }
 };
 
@@ -719,73 +804,87 @@ struct BoxIndex {
   }
 };
 
-void Fmm::build(const double* dx, const double* dy, const double* dwnx, const double* dwny, int64_t n,
-                double kap, int order, int lmax, const double* tab, hipStream_t s) {
+Fmm::~Fmm() {
+  if (dn_done) (void)hipEventDestroy(dn_done);
+}
+
+void Fmm::download(const double* dx, const double* dy, const double* dwnx, const double* dwny,
+                   int64_t n, hipStream_t s) {
+  YQ_REQUIRE(n >= 1 && n < ((int64_t)1 << 31), YQ_EINVAL, "FMM: node count out of range");
+  static_assert(2 * DMAX <= 32, "Morton keys must fit 32 bits");
+  const unsigned nb = (unsigned)((n + 255) / 256);
+  bbox.fit(4);
+  keys.fit(n);
+  skeys.fit(n);
+  iota.fit(n);
+  perm.fit(n);
+  bbox_kernel<<<1, BBOX_BS, 0, s>>>(dx, dy, n, bbox.p);
+  keys_kernel<<<nb, 256, 0, s>>>(dx, dy, n, bbox.p, DMAX, keys.p, iota.p);
+  YQ_HIP(hipGetLastError());
+  size_t tmp_bytes = 0;
+  YQ_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_bytes, keys.p, skeys.p, iota.p, perm.p,
+                                            (int)n, 0, 2 * DMAX, s));
+  sort_tmp.fit(std::max<size_t>(tmp_bytes, 1));
+  // stable: equal keys keep ascending node order
+  YQ_HIP(hipcub::DeviceRadixSort::SortPairs(sort_tmp.p, tmp_bytes, keys.p, skeys.p, iota.p, perm.p,
+                                            (int)n, 0, 2 * DMAX, s));
+  xs.fit(n);
+  ys.fit(n);
+  wnxs.fit(n);
+  wnys.fit(n);
+  sort_gather_kernel<<<nb, 256, 0, s>>>(n, perm.p, dx, dy, dwnx, dwny, xs.p, ys.p, wnxs.p, wnys.p);
+  YQ_HIP(hipGetLastError());
+  stage_dn.fit((size_t)n * sizeof(uint32_t) + 4 * sizeof(double));
+  YQ_HIP(hipMemcpyAsync(stage_dn.p, bbox.p, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+  YQ_HIP(hipMemcpyAsync(stage_dn.p + 4 * sizeof(double), skeys.p, n * sizeof(uint32_t),
+                        hipMemcpyDeviceToHost, s));
+  if (!dn_done) YQ_HIP(hipEventCreateWithFlags(&dn_done, hipEventDisableTiming));
+  YQ_HIP(hipEventRecord(dn_done, s));
+  N = n;
+}
+
+void Fmm::build(int64_t n, double kap, int order, int lmax, const double* tab, hipStream_t s) {
   YQ_REQUIRE(order >= 1 && order <= MAXP_FMM, YQ_EINVAL, "FMM order must be in 1..48");
   YQ_REQUIRE(lmax >= 1, YQ_EINVAL, "fmm_leaf_max must be >= 1");
+  YQ_REQUIRE(dn_done && n == N && stage_dn.cap >= (size_t)n * sizeof(uint32_t) + 4 * sizeof(double),
+             YQ_ESTATE, "FMM: build without a matching download");
   p = order;
   leaf_max = lmax;
   kappa = kap;
-  N = n;
-  Uploader up(s);
-  std::vector<double> hx(n), hy(n), hwx(n), hwy(n);
-  YQ_HIP(hipMemcpyAsync(hx.data(), dx, n * sizeof(double), hipMemcpyDeviceToHost, s));
-  YQ_HIP(hipMemcpyAsync(hy.data(), dy, n * sizeof(double), hipMemcpyDeviceToHost, s));
-  YQ_HIP(hipMemcpyAsync(hwx.data(), dwnx, n * sizeof(double), hipMemcpyDeviceToHost, s));
-  YQ_HIP(hipMemcpyAsync(hwy.data(), dwny, n * sizeof(double), hipMemcpyDeviceToHost, s));
-  YQ_HIP(hipStreamSynchronize(s));
-  double xmin = hx[0], xmax = hx[0], ymin = hy[0], ymax = hy[0];
-  for (int64_t i = 0; i < n; ++i) {
-    xmin = std::min(xmin, hx[i]);
-    xmax = std::max(xmax, hx[i]);
-    ymin = std::min(ymin, hy[i]);
-    ymax = std::max(ymax, hy[i]);
-  }
-  W = std::max(xmax - xmin, ymax - ymin) * (1.0 + 1e-9) + 1e-12;
-  x0 = 0.5 * (xmin + xmax) - 0.5 * W;
-  y0 = 0.5 * (ymin + ymax) - 0.5 * W;
-  // Morton keys at the finest candidate depth, sorted once; a coarser level's key
-  // is a right shift, so its occupancy is a linear scan of the sorted keys.
-  YQ_REQUIRE(n < (int64_t)1 << 31, YQ_EINVAL, "FMM: too many nodes");
-  std::vector<int64_t> kmax(n);
-  std::vector<uint64_t> packed(n);
+  Uploader up(s, stage_up);
+  YQ_HIP(hipEventSynchronize(dn_done));
+  root_box(reinterpret_cast<const double*>(stage_dn.p), W, x0, y0);
+  const uint32_t* skey = reinterpret_cast<const uint32_t*>(stage_dn.p + 4 * sizeof(double));
+  // Depth: occupied boxes per level in one pass over the sorted keys.  Sorted
+  // neighbours k-1, k fall in different boxes at level d exactly when the
+  // highest differing bit of their keys is at or above bit 2 (DMAX - d), i.e.
+  // from level DMAX - msb/2 on.
   {
-    const int64_t m = 1LL << DMAX;
-    for (int64_t i = 0; i < n; ++i) {
-      int64_t ix = (int64_t)((hx[i] - x0) / W * m), iy = (int64_t)((hy[i] - y0) / W * m);
-      ix = std::min(std::max(ix, (int64_t)0), m - 1);
-      iy = std::min(std::max(iy, (int64_t)0), m - 1);
-      kmax[i] = morton(ix, iy);
-      packed[i] = ((uint64_t)kmax[i] << 32) | (uint64_t)i;
+    std::vector<int64_t> first(DMAX + 2, 0);
+    for (int64_t k = 1; k < n; ++k) {
+      const uint32_t x = skey[k] ^ skey[k - 1];
+      if (!x) continue;
+      const int msb = 31 - __builtin_clz(x);
+      ++first[DMAX - msb / 2];
     }
-  }
-  radix_sort_keys(packed, 2 * DMAX);
-  std::vector<int> order_idx(n);
-  for (int64_t k = 0; k < n; ++k) order_idx[k] = (int)(packed[k] & 0xffffffffULL);
-  depth = DMAX;
-  for (int d = 2; d <= DMAX; ++d) {
-    const int sh = 2 * (DMAX - d);
-    int64_t occ = 0, last = -1;
-    for (int64_t k = 0; k < n; ++k) {
-      const int64_t kk = kmax[order_idx[k]] >> sh;
-      if (kk != last) {
-        ++occ;
-        last = kk;
+    depth = DMAX;
+    int64_t occ = 1;
+    for (int d = 0; d <= DMAX; ++d) {
+      occ += first[d];
+      if (d >= 2 && (double)n / occ <= (double)leaf_max) {
+        depth = d;
+        break;
       }
-    }
-    if ((double)n / occ <= (double)leaf_max) {
-      depth = d;
-      break;
     }
   }
   const int shl = 2 * (DMAX - depth);
-  lv.clear();
-  lv.resize(depth + 1);
+  lv.resize(depth + 1);   // levels keep their device buffers from earlier builds
+  for (auto& L : lv) L.key.clear();
   std::vector<int> hls, hlc;
   {
     FmmLevel& L = lv[depth];
     for (int64_t k = 0; k < n; ++k) {
-      const int64_t kk = kmax[order_idx[k]] >> shl;
+      const int64_t kk = (int64_t)(skey[k] >> shl);
       if (L.key.empty() || L.key.back() != kk) {
         L.key.push_back(kk);
         hls.push_back((int)k);
@@ -794,68 +893,86 @@ void Fmm::build(const double* dx, const double* dy, const double* dwnx, const do
       ++hlc.back();
     }
   }
-  for (int l = depth - 1; l >= 0; --l) {
-    std::vector<int64_t>& ck = lv[l + 1].key;
-    for (int64_t k : ck) {
-      const int64_t pk = k >> 2;
-      if (lv[l].key.empty() || lv[l].key.back() != pk) lv[l].key.push_back(pk);
+  // parents: level l - 1 holds the distinct (key >> 2) of level l, in order
+  std::vector<std::vector<int>> par(depth + 1);
+  for (int l = depth; l >= 1; --l) {
+    std::vector<int64_t>& ck = lv[l].key;
+    std::vector<int64_t>& pk = lv[l - 1].key;
+    par[l].resize(ck.size());
+    for (size_t b = 0; b < ck.size(); ++b) {
+      if (pk.empty() || pk.back() != (ck[b] >> 2)) pk.push_back(ck[b] >> 2);
+      par[l][b] = (int)pk.size() - 1;
     }
   }
   max_leaf = *std::max_element(hlc.begin(), hlc.end());
-  std::vector<BoxIndex> idx(depth + 1);
+  // per level: grid coordinates, children, colleagues (the <= 9 adjacent boxes of
+  // the same level, the box itself included, in (dx, dy) order, -1 where none)
+  std::vector<std::vector<int>> bx(depth + 1), by(depth + 1), chl(depth + 1), col(depth + 1);
   for (int l = 0; l <= depth; ++l) {
     FmmLevel& L = lv[l];
     L.nbox = (int)L.key.size();
     L.w = W / (double)(1LL << l);
-    idx[l].init(l, L.key);
+    bx[l].resize(L.nbox);
+    by[l].resize(L.nbox);
+    for (int b = 0; b < L.nbox; ++b) {
+      int64_t ix, iy;
+      unmorton(L.key[b], ix, iy);
+      bx[l][b] = (int)ix;
+      by[l][b] = (int)iy;
+    }
+    chl[l].assign(4 * (size_t)L.nbox, -1);
+  }
+  for (int l = 1; l <= depth; ++l)
+    for (int c = 0; c < lv[l].nbox; ++c) chl[l - 1][4 * (size_t)par[l][c] + (lv[l].key[c] & 3)] = c;
+  for (int l = 0; l <= depth; ++l) {
+    BoxIndex idx;
+    idx.init(l, lv[l].key);
+    const int64_t lim = 1LL << l;
+    col[l].assign(9 * (size_t)lv[l].nbox, -1);
+    for (int b = 0; b < lv[l].nbox; ++b)
+      for (int ddx = -1; ddx <= 1; ++ddx)
+        for (int ddy = -1; ddy <= 1; ++ddy) {
+          const int64_t qx_ = bx[l][b] + ddx, qy_ = by[l][b] + ddy;
+          if (qx_ < 0 || qy_ < 0 || qx_ >= lim || qy_ >= lim) continue;
+          col[l][9 * (size_t)b + (ddx + 1) * 3 + (ddy + 1)] = idx.find(morton(qx_, qy_));
+        }
   }
   std::vector<int> hnbp(1, 0), hnbi;
   for (int l = 0; l <= depth; ++l) {
     FmmLevel& L = lv[l];
     std::vector<double> hcx(L.nbox), hcy(L.nbox);
-    std::vector<int> hpar(L.nbox, -1), hpos(L.nbox, 0), hch(4 * (size_t)L.nbox, -1);
+    std::vector<int> hpar(L.nbox, -1), hpos(L.nbox, 0);
     std::vector<int> ilp(1, 0), ils, ilo;
     for (int b = 0; b < L.nbox; ++b) {
-      int64_t ix, iy;
-      unmorton(L.key[b], ix, iy);
+      const int ix = bx[l][b], iy = by[l][b];
       hcx[b] = x0 + (ix + 0.5) * L.w;
       hcy[b] = y0 + (iy + 0.5) * L.w;
       if (l > 0) {
-        hpar[b] = idx[l - 1].find(L.key[b] >> 2);
+        hpar[b] = par[l][b];
         hpos[b] = (int)(L.key[b] & 3);
       }
-      if (l < depth)
-        for (int pos = 0; pos < 4; ++pos) hch[4 * (size_t)b + pos] = idx[l + 1].find((L.key[b] << 2) | pos);
       if (l >= 2) {
-        int64_t px, py;
-        unmorton(L.key[b] >> 2, px, py);
-        const int64_t lim = 1LL << (l - 1);
-        for (int ddx = -1; ddx <= 1; ++ddx)
-          for (int ddy = -1; ddy <= 1; ++ddy) {
-            if (px + ddx < 0 || py + ddy < 0 || px + ddx >= lim || py + ddy >= lim) continue;
-            const int pb = idx[l - 1].find(morton(px + ddx, py + ddy));
-            if (pb < 0) continue;
-            for (int pos = 0; pos < 4; ++pos) {
-              const int sb = idx[l].find((lv[l - 1].key[pb] << 2) | pos);
-              if (sb < 0) continue;
-              int64_t sx, sy;
-              unmorton(lv[l].key[sb], sx, sy);
-              const int64_t ox = sx - ix, oy = sy - iy;
-              if (std::llabs(ox) <= 1 && std::llabs(oy) <= 1) continue;
-              ils.push_back(sb);
-              ilo.push_back((int)((ox + 3) * 7 + (oy + 3)));
-            }
+        // interaction list: children of the parent's colleagues that are not
+        // adjacent to the box
+        const int* pc = &col[l - 1][9 * (size_t)par[l][b]];
+        for (int e = 0; e < 9; ++e) {
+          if (pc[e] < 0) continue;
+          for (int pos = 0; pos < 4; ++pos) {
+            const int sb = chl[l - 1][4 * (size_t)pc[e] + pos];
+            if (sb < 0) continue;
+            const int ox = bx[l][sb] - ix, oy = by[l][sb] - iy;
+            if (std::abs(ox) <= 1 && std::abs(oy) <= 1) continue;
+            ils.push_back(sb);
+            ilo.push_back((ox + 3) * 7 + (oy + 3));
           }
+        }
         ilp.push_back((int)ils.size());
       }
       if (l == depth) {
-        const int64_t lim = 1LL << l;
-        for (int ddx = -1; ddx <= 1; ++ddx)
-          for (int ddy = -1; ddy <= 1; ++ddy) {
-            if (ix + ddx < 0 || iy + ddy < 0 || ix + ddx >= lim || iy + ddy >= lim) continue;
-            const int nb = idx[l].find(morton(ix + ddx, iy + ddy));
-            if (nb >= 0) hnbi.push_back(nb);
-          }
+        for (int e = 0; e < 9; ++e) {
+          const int nb = col[l][9 * (size_t)b + e];
+          if (nb >= 0) hnbi.push_back(nb);
+        }
         hnbp.push_back((int)hnbi.size());
       }
     }
@@ -863,7 +980,7 @@ void Fmm::build(const double* dx, const double* dy, const double* dwnx, const do
     up(L.cy, hcy);
     up(L.parent, hpar);
     up(L.cpos, hpos);
-    up(L.ch, hch);
+    up(L.ch, chl[l]);
     if (l >= 2) {
       up(L.ilp, ilp);
       up(L.ils, ils);
@@ -878,21 +995,8 @@ void Fmm::build(const double* dx, const double* dy, const double* dwnx, const do
   up(leaf_cnt, hlc);
   up(nbp, hnbp);
   up(nbi, hnbi);
-  std::vector<double> sx(n), sy(n), swx(n), swy(n);
-  for (int64_t k = 0; k < n; ++k) {
-    const int i = order_idx[k];
-    sx[k] = hx[i];
-    sy[k] = hy[i];
-    swx[k] = hwx[i];
-    swy[k] = hwy[i];
-  }
-  up(perm, order_idx);
-  up(xs, sx);
-  up(ys, sy);
-  up(wnxs, swx);
-  up(wnys, swy);
-  qx.alloc(n);
-  qy.alloc(n);
+  qx.fit(n);
+  qy.fit(n);
   up.finish();
   set_order(order, tab, s);
 }
@@ -902,28 +1006,28 @@ void Fmm::set_order(int q, const double* tab, hipStream_t s) {
   YQ_REQUIRE(q >= 1 && q <= MAXP_FMM, YQ_EINVAL, "FMM order must be in 1..48");
   p = q;
   for (auto& L : lv) {
-    L.M.alloc((size_t)std::max(L.nbox, 1) * (p + 1));
-    L.L.alloc((size_t)std::max(L.nbox, 1) * (p + 1));
+    L.M.fit((size_t)std::max(L.nbox, 1) * (p + 1));
+    L.L.fit((size_t)std::max(L.nbox, 1) * (p + 1));
   }
   const int K = 4 * p + 1;
-  tg.alloc((size_t)(depth + 1) * 4 * K);
-  ts.alloc((size_t)(depth + 1) * 49 * K);
+  tg.fit((size_t)(depth + 1) * 4 * K);
+  ts.fit((size_t)(depth + 1) * 49 * K);
   tab_g_kernel<<<(depth + 1) * 4, TAB_BS, 0, s>>>(p, W, kappa, tg.p);
   tab_s_kernel<<<(depth + 1) * 49, TAB_BS, 0, s>>>(p, W, kappa, tab, ts.p);
   YQ_HIP(hipGetLastError());
   R16 = ((2 * (p + 1) + 15) / 16) * 16;
   if (use_mfma) {
     const int64_t vals = (int64_t)(depth + 1) * 49 * R16 * R16;
-    amat.alloc((size_t)vals);
+    amat.fit((size_t)vals);
     trans_amat_kernel<<<(unsigned)((vals + 255) / 256), 256, 0, s>>>(depth + 1, 49, p, R16, 1, ts.p,
                                                                        amat.p);
     const int64_t gvals = (int64_t)(depth + 1) * 4 * R16 * R16;
-    gmat.alloc((size_t)gvals);
+    gmat.fit((size_t)gvals);
     trans_amat_kernel<<<(unsigned)((gvals + 255) / 256), 256, 0, s>>>(depth + 1, 4, p, R16, 0, tg.p,
                                                                         gmat.p);
     YQ_HIP(hipGetLastError());
     // 16-box tiles of every level with M2L terms, finest level first
-    Uploader up(s);
+    Uploader up(s, stage_up);
     std::vector<int2> ht;
     for (int l = depth; l >= 2; --l)
       for (int b = 0; b < lv[l].nbox; b += 16) ht.push_back(make_int2(l, b));
@@ -939,7 +1043,7 @@ void Fmm::set_order(int q, const double* tab, hipStream_t s) {
 void Fmm::copy_tree(const Fmm& o, int q, const double* tab, hipStream_t s) {
   auto dup = [&](auto& dst, const auto& src) {
     using T = std::remove_pointer_t<decltype(src.p)>;
-    dst.alloc(std::max<size_t>(src.n, 1));
+    dst.fit(std::max<size_t>(src.n, 1));
     if (src.n) YQ_HIP(hipMemcpyAsync(dst.p, src.p, src.n * sizeof(T), hipMemcpyDeviceToDevice, s));
   };
   depth = o.depth;
@@ -950,7 +1054,6 @@ void Fmm::copy_tree(const Fmm& o, int q, const double* tab, hipStream_t s) {
   kappa = o.kappa;
   N = o.N;
   max_leaf = o.max_leaf;
-  lv.clear();
   lv.resize(o.lv.size());
   for (size_t l = 0; l < o.lv.size(); ++l) {
     lv[l].nbox = o.lv[l].nbox;
@@ -977,8 +1080,8 @@ void Fmm::copy_tree(const Fmm& o, int q, const double* tab, hipStream_t s) {
   dup(leaf_cnt, o.leaf_cnt);
   dup(nbp, o.nbp);
   dup(nbi, o.nbi);
-  qx.alloc(N);
-  qy.alloc(N);
+  qx.fit(N);
+  qy.fit(N);
   set_order(q, tab, s);
 }
 

@@ -33,7 +33,7 @@ struct yq_problem {
   DevBuf<float2> frel;
   DevBuf<float4> fsrc;
   DevBuf<double> pot_partial;
-  DevBuf<int> nb_ptr, nb_idx, bad;
+  DevBuf<int> nb_ptr, nb_idx, bad, ncnt;
   DevBuf<int> xrow, xpan;
   int64_t x_total = 0;
   DevBuf<double> xvals, xgvals;
@@ -47,6 +47,7 @@ struct yq_problem {
   // Krylov workspace
   DevBuf<double> V, kw, kr, kd, kpart, kred;
   DevBuf<double> gx, gy, en;
+  DevBuf<double> delta;   // refinement correction
 
   // per-phase timers
   static constexpr int NPHASE = 6;
