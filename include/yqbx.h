@@ -56,7 +56,7 @@ enum { YQ_FP64 = 0, YQ_MIXED = 1 };                       /* precision */
 enum { YQ_FMM64 = 2 };  /* yq_apply_far only: FMM expansions with FP64 near interactions */
 enum { YQ_FAR_DIRECT = 0, YQ_FAR_FMM = 1, YQ_FAR_AUTO = 2 };   /* far-field mode */
 enum { YQ_LABEL_ARC = 0, YQ_LABEL_JANUS = 1 };             /* boundary labels */
-enum { YQ_M2L_MFMA = 0, YQ_M2L_VALU = 1 };                 /* FMM M2L kernel */
+enum { YQ_M2L_MFMA = 0, YQ_M2L_VALU = 1, YQ_M2L_MFMA64 = 2 };   /* FMM translation kernels */
 
 typedef struct yq_problem yq_problem;
 
@@ -82,9 +82,12 @@ typedef struct yq_params {
   int32_t fmm_resid_order;     /* FMM enabled: order of the FP64 FMM used for refinement residuals,
                                   FP64 solves and the reported residual (relative operator error
                                   ~1e-10 at 40); 0 = the exact direct sum */
-  int32_t fmm_m2l;             /* FMM M2M/M2L/L2L translations: YQ_M2L_MFMA (FP64 matrix-core
-                                  products) or YQ_M2L_VALU (one lane per coefficient); the same
-                                  results to rounding */
+  int32_t fmm_m2l;             /* FMM M2M/M2L/L2L translations: YQ_M2L_MFMA (matrix-core products;
+                                  the M2L of the FP32-class inner operator in FP32 on scaled
+                                  expansions, everything else in FP64), YQ_M2L_MFMA64 (all
+                                  translations FP64 on the matrix cores) or YQ_M2L_VALU (FP64, one
+                                  lane per coefficient; the same results as YQ_M2L_MFMA64 to
+                                  rounding) */
 } yq_params;
 
 typedef struct yq_solve_info {

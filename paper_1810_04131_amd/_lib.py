@@ -25,6 +25,7 @@ YQ_LABEL_ARC = 0
 YQ_LABEL_JANUS = 1
 YQ_M2L_MFMA = 0
 YQ_M2L_VALU = 1
+YQ_M2L_MFMA64 = 2
 
 c_int32 = ctypes.c_int32
 c_int64 = ctypes.c_int64

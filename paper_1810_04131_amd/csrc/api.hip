@@ -76,7 +76,8 @@ void check_params(const yq_params& p) {
   YQ_REQUIRE(p.fmm_resid_order >= 0 && p.fmm_resid_order <= MAXP_FMM, YQ_EINVAL,
              "fmm_resid_order out of range 0..48");
   YQ_REQUIRE(p.fmm_leaf_max >= 1, YQ_EINVAL, "fmm_leaf_max must be >= 1");
-  YQ_REQUIRE(p.fmm_m2l == YQ_M2L_MFMA || p.fmm_m2l == YQ_M2L_VALU, YQ_EINVAL, "bad fmm_m2l");
+  YQ_REQUIRE(p.fmm_m2l == YQ_M2L_MFMA || p.fmm_m2l == YQ_M2L_VALU || p.fmm_m2l == YQ_M2L_MFMA64,
+             YQ_EINVAL, "bad fmm_m2l");
   YQ_REQUIRE(p.tol > 0.0 && p.maxiter >= 1 && p.restart >= 1 && p.restart <= 200, YQ_EINVAL,
              "tol > 0, maxiter >= 1, 1 <= restart <= 200");
   YQ_REQUIRE(p.inner_tol > 0.0 && p.inner_tol < 1.0 && p.max_refine >= 1, YQ_EINVAL,
@@ -559,11 +560,13 @@ int yq_set_particles(yq_problem* pb, int32_t n, const double* center_xy, const d
 
     pb->fp = far_plan(N, N, 256, pb->far_want);
     if (use_fmm) {
-      pb->fmm->use_mfma = pb->prm.fmm_m2l == YQ_M2L_MFMA;
+      pb->fmm->use_mfma = pb->prm.fmm_m2l != YQ_M2L_VALU;
+      pb->fmm->want_m2l32 = pb->prm.fmm_m2l == YQ_M2L_MFMA;
       pb->fmm->build(N, kappa, pb->prm.fmm_order, pb->prm.fmm_leaf_max, pb->tab.p, s);
       if (pb->prm.fmm_resid_order > 0) {
         if (!pb->fmm_hi) pb->fmm_hi = std::make_unique<Fmm>();
-        pb->fmm_hi->use_mfma = pb->prm.fmm_m2l == YQ_M2L_MFMA;
+        pb->fmm_hi->use_mfma = pb->prm.fmm_m2l != YQ_M2L_VALU;
+        pb->fmm_hi->want_m2l32 = false;
         pb->fmm_hi->copy_tree(*pb->fmm, pb->prm.fmm_resid_order, pb->tab.p, s);
       } else {
         pb->fmm_hi.reset();

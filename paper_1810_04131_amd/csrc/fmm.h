@@ -41,6 +41,11 @@ struct Fmm {
   DevBuf<double> gmat;    // M2M / L2L matrices [level][child position][R16 * R16], same order
   DevBuf<int2> m2l_tiles; // (level, first box) of every 16-box M2L tile
   int n_m2l_tiles = 0;
+  // FP32 M2L for the inner (FP32-class) applies: with s_n = n! (2 / (kappa w))^n per
+  // level, the products run on M_n s_n and A_mn / (s_m s_n) in FP32 and give L_m / s_m
+  bool want_m2l32 = false;
+  DevBuf<float> amat32;   // scaled M2L matrices, the operand order of amat
+  DevBuf<double> msc;     // s_n per level [level][n]
   PinnedBuf stage_up, stage_dn;   // set-up transfers (grow-only, reused by every build)
   DevBuf<double> bbox;            // node bounding box (xmin, xmax, ymin, ymax)
   DevBuf<uint32_t> keys, skeys;   // finest-level Morton keys, unsorted / sorted
@@ -64,8 +69,9 @@ struct Fmm {
   void copy_tree(const Fmm& o, int q, const double* tab, hipStream_t s);
   // partial[i] = (2 pi / kappa^2) * far field at node i (the far-field kernels' scaling)
   void m2l_mfma(hipStream_t s);
+  void m2l_mfma32(hipStream_t s);
   void tree_mfma(bool gather, int l, hipStream_t s);
-  void expansions(const double* sigma, hipStream_t s);
+  void expansions(const double* sigma, hipStream_t s, bool m2l32 = false);
   // gpart[i], gpart[N + i] = (2 pi / kappa^2) * gradient of the far field at node i (FP64)
   void apply_grad(const double* sigma, double* gpart, const double* tab, hipStream_t s);
   void apply(const double* sigma, double* partial, bool p2p_fp32, const double* tab,

@@ -273,6 +273,7 @@ __global__ void m2l_kernel(int p, int nbox, const int* __restrict__ ilp, const i
 // accumulates A_o B with v_mfma_f64_16x16x4f64 (FP64, so the FMM keeps its
 // accuracy).  All levels go in one launch: their M2L terms are independent.
 typedef double dbl4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 constexpr int DMAX = 14;   // deepest quadtree level
 
 // Translation matrices in the operand order of the 16x16x4 product: for
@@ -416,6 +417,102 @@ __global__ __launch_bounds__(256) void m2l_mfma_kernel(int p, const int2* __rest
   }
   acc = block_tile_sum(acc, red);
   if (wave == 0 && tb < nbox) tile_store<false>(lv.L[l] + (int64_t)tb * P1, rt, kk, P1, acc);
+}
+
+// Scaled FP32 copy of the M2L matrices (operand order as in trans_amat_kernel):
+// amat32 = A_mn / (s_m s_n), s = msc of the matrix's level.
+__global__ void trans_amat32_kernel(int nlev, int p, int R, const double* __restrict__ amat,
+                                    const double* __restrict__ msc, float* __restrict__ amat32) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t per = (int64_t)R * R;
+  if (t >= (int64_t)nlev * 49 * per) return;
+  const int l = (int)(t / (49 * per));
+  const int rem = (int)(t % per);
+  const int lane = rem & 63, tile = rem >> 6;
+  const int rt = tile / (R / 4), ks = tile % (R / 4);
+  const int r = 16 * rt + (lane & 15), k = 4 * ks + (lane >> 4);
+  const int P1 = p + 1;
+  float v = 0.0f;
+  if (r < 2 * P1 && k < 2 * P1) {
+    const double* sc = msc + (int64_t)l * P1;
+    v = (float)(amat[t] / (sc[r < P1 ? r : r - P1] * sc[k < P1 ? k : k - P1]));
+  }
+  amat32[t] = v;
+}
+
+// FP32 counterpart of m2l_mfma_kernel (inner applies only): B operands are the
+// scaled multipole coefficients M_n s_n rounded to FP32, products accumulate in
+// FP32 (v_mfma_f32_16x16x4f32), the four waves' tiles are summed in FP64 and
+// L_m = (sum) s_m is stored in FP64.  FP32 16x16 result layout: lane l holds
+// column l % 16, its register j row 4 (l / 16) + j.
+template <int RT>
+__global__ __launch_bounds__(256) void m2l_mfma32_kernel(int p, const int2* __restrict__ tiles,
+                                                         M2LLevels lv,
+                                                         const float* __restrict__ amat32,
+                                                         int64_t level_stride,
+                                                         const double* __restrict__ msc) {
+  constexpr int R = RT * 16, KS = R / 4, NI = 10;
+  __shared__ dbl4 red[3 * 64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int2 tl = tiles[blockIdx.x / RT];
+  const int rt = blockIdx.x % RT;
+  const int l = tl.x, nbox = lv.nbox[l];
+  const int* __restrict__ ild = lv.ild[l];
+  const double2* __restrict__ M = lv.M[l];
+  const int P1 = p + 1;
+  const double* sc = msc + (int64_t)l * P1;
+  const int col = lane & 15, kk = lane >> 4;
+  const int tb = tl.y + col;
+  const float* Al = amat32 + l * level_stride + (int64_t)rt * KS * 64 + lane;
+  double bs[KS];   // scale of this lane's B rows
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) {
+    const int k = 4 * ks + kk;
+    bs[ks] = k < 2 * P1 ? sc[k < P1 ? k : k - P1] : 0.0;
+  }
+  int src[NI];
+#pragma unroll
+  for (int i = 0; i < NI; ++i) src[i] = tb < nbox ? ild[(int64_t)tb * 49 + far_offset(wave + 4 * i)] : -1;
+  f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+  float a0[KS], b0[KS], a1[KS], b1[KS];
+  auto load = [&](int i, float* a, float* b) {
+    const float* A = Al + (int64_t)far_offset(wave + 4 * i) * R * R;
+    const double2* ms = src[i] >= 0 ? M + (int64_t)src[i] * P1 : nullptr;
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      a[ks] = A[ks * 64];
+      const int k = 4 * ks + kk;
+      double v = 0.0;
+      if (ms != nullptr && k < 2 * P1) {
+        const double2 mv = ms[k < P1 ? k : k - P1];
+        v = (k < P1 ? mv.x : mv.y) * bs[ks];
+      }
+      b[ks] = (float)v;
+    }
+  };
+  load(0, a0, b0);
+#pragma unroll
+  for (int i = 0; i < NI; i += 2) {
+    load(i + 1, a1, b1);
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[ks], b0[ks], acc, 0, 0, 0);
+    if (i + 2 < NI) load(i + 2, a0, b0);
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[ks], b1[ks], acc, 0, 0, 0);
+  }
+  dbl4 acd = {(double)acc[0], (double)acc[1], (double)acc[2], (double)acc[3]};
+  acd = block_tile_sum(acd, red);
+  if (wave == 0 && tb < nbox) {
+    double2* y = lv.L[l] + (int64_t)tb * P1;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int r = rt * 16 + 4 * kk + j;
+      if (r < P1)
+        y[r].x = acd[j] * sc[r];
+      else if (r < 2 * P1)
+        y[r - P1].y = acd[j] * sc[r - P1];
+    }
+  }
 }
 
 // M2M (GATHER: parent tiles at level l, y = sum over the 4 children of A_pos x_child)
@@ -1032,8 +1129,24 @@ void Fmm::set_order(int q, const double* tab, hipStream_t s) {
     for (int l = depth; l >= 2; --l)
       for (int b = 0; b < lv[l].nbox; b += 16) ht.push_back(make_int2(l, b));
     up(m2l_tiles, ht);
+    if (want_m2l32) {
+      // s_n = n! (2 / (kappa w_l))^n, in logarithms (the factors themselves span
+      // hundreds of decades across levels and orders; each stays within FP64)
+      std::vector<double> hs((size_t)(depth + 1) * (p + 1));
+      for (int l = 0; l <= depth; ++l)
+        for (int n = 0; n <= p; ++n)
+          hs[(size_t)l * (p + 1) + n] =
+              std::exp(std::lgamma(n + 1.0) + n * std::log(2.0 / (kappa * lv[l].w)));
+      up(msc, hs);
+      amat32.fit((size_t)vals);
+    }
     up.finish();
     n_m2l_tiles = (int)ht.size();
+    if (want_m2l32) {
+      trans_amat32_kernel<<<(unsigned)((vals + 255) / 256), 256, 0, s>>>(depth + 1, p, R16, amat.p,
+                                                                         msc.p, amat32.p);
+      YQ_HIP(hipGetLastError());
+    }
   }
   YQ_HIP(hipStreamSynchronize(s));
   built = true;
@@ -1109,6 +1222,30 @@ void Fmm::m2l_mfma(hipStream_t s) {
   YQ_HIP(hipGetLastError());
 }
 
+void Fmm::m2l_mfma32(hipStream_t s) {
+  M2LLevels a{};
+  for (int l = 2; l <= depth; ++l) {
+    a.ild[l] = lv[l].ild.p;
+    a.M[l] = lv[l].M.p;
+    a.L[l] = lv[l].L.p;
+    a.nbox[l] = lv[l].nbox;
+  }
+  const int RT = R16 / 16;
+  const unsigned g = (unsigned)(n_m2l_tiles * RT);
+  if (g == 0) return;
+  const int64_t ls = (int64_t)49 * R16 * R16;
+  switch (RT) {
+    case 1: m2l_mfma32_kernel<1><<<g, 256, 0, s>>>(p, m2l_tiles.p, a, amat32.p, ls, msc.p); break;
+    case 2: m2l_mfma32_kernel<2><<<g, 256, 0, s>>>(p, m2l_tiles.p, a, amat32.p, ls, msc.p); break;
+    case 3: m2l_mfma32_kernel<3><<<g, 256, 0, s>>>(p, m2l_tiles.p, a, amat32.p, ls, msc.p); break;
+    case 4: m2l_mfma32_kernel<4><<<g, 256, 0, s>>>(p, m2l_tiles.p, a, amat32.p, ls, msc.p); break;
+    case 5: m2l_mfma32_kernel<5><<<g, 256, 0, s>>>(p, m2l_tiles.p, a, amat32.p, ls, msc.p); break;
+    case 6: m2l_mfma32_kernel<6><<<g, 256, 0, s>>>(p, m2l_tiles.p, a, amat32.p, ls, msc.p); break;
+    default: m2l_mfma32_kernel<7><<<g, 256, 0, s>>>(p, m2l_tiles.p, a, amat32.p, ls, msc.p); break;
+  }
+  YQ_HIP(hipGetLastError());
+}
+
 // M2M into parent level l (gather) or L2L from parent level l (scatter), both
 // with the child level's position matrices.
 void Fmm::tree_mfma(bool gather, int l, hipStream_t s) {
@@ -1140,7 +1277,7 @@ void Fmm::tree_mfma(bool gather, int l, hipStream_t s) {
 
 // Multipole and local expansions of the leaves for density sigma (upward pass,
 // M2L, downward pass).
-void Fmm::expansions(const double* sigma, hipStream_t s) {
+void Fmm::expansions(const double* sigma, hipStream_t s, bool m2l32) {
   YQ_REQUIRE(built, YQ_ESTATE, "FMM tree not built");
   const int K = 4 * p + 1;
   gather_kernel<<<(unsigned)((N + 255) / 256), 256, 0, s>>>(N, perm.p, sigma, wnxs.p, wnys.p, qx.p,
@@ -1158,7 +1295,9 @@ void Fmm::expansions(const double* sigma, hipStream_t s) {
                                                             tg.p + (size_t)(l + 1) * 4 * K,
                                                             lv[l].M.p);
   }
-  if (use_mfma) {
+  if (use_mfma && m2l32) {
+    m2l_mfma32(s);
+  } else if (use_mfma) {
     m2l_mfma(s);
   } else {
     for (int l = 2; l <= depth; ++l) {
@@ -1183,7 +1322,8 @@ void Fmm::expansions(const double* sigma, hipStream_t s) {
 
 void Fmm::apply(const double* sigma, double* partial, bool p2p_fp32, const double* tab,
                 hipStream_t s) {
-  expansions(sigma, s);
+  // the FP32-class (inner) operator also takes its M2L in FP32 when that is set up
+  expansions(sigma, s, p2p_fp32 && want_m2l32 && use_mfma);
   FmmLevel& leaf = lv[depth];
   const size_t sh_l = (size_t)FB * (2 * sizeof(double2) + sizeof(float2));
   if (p2p_fp32)

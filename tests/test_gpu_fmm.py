@@ -142,3 +142,20 @@ def test_fmm_large_workload_residual_property():
     rows = sorted(set(np.random.default_rng(2).integers(0, d.N, 8).tolist()))
     r = oracle.apply_rows(d, rows, _np(sig)) - oracle.arc_label(d)[rows]
     assert np.abs(r).max() < 1e-6
+
+
+@pytest.mark.parametrize("order,kappa", [(8, 1.0), (20, 0.5), (20, 2.0), (30, 1.0)])
+def test_fmm_fp32_m2l_matches_fp64_m2l(order, kappa):
+    # the inner operator's M2L in FP32 on scaled expansions against the same
+    # operator with FP64 translations: the FP32 products change it by a relative
+    # amount at the FP32 level, well below the order-20 truncation error
+    _torch()
+    parts = workloads.config_medium(kappa=kappa, seed=2)["particles"]
+    sig = workloads.random_density(25600, 9)
+    out = {}
+    for m2l in (yq.YQ_M2L_MFMA, yq.YQ_M2L_MFMA64):
+        pb = yq.Problem(yq.default_params(far_mode=yq.YQ_FAR_FMM, fmm_order=order, fmm_leaf_max=64,
+                                          fmm_m2l=m2l))
+        pb.set_workload(parts)
+        out[m2l] = _np(pb.apply_far(sig, yq.YQ_MIXED))
+    assert _rel(out[yq.YQ_M2L_MFMA], out[yq.YQ_M2L_MFMA64]) < 2e-6

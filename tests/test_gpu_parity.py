@@ -279,3 +279,23 @@ def test_errors_and_edges():
     with pytest.raises(yq.YQError) as e:
         pb.solve()
     assert e.value.status == _lib.YQ_ENOCONV
+
+
+# ---- the paper's printed single-disk table (golden fixture) ----------------------------------
+
+@pytest.mark.parametrize("precision,tol", [(0, 1e-13), (1, 1e-10)])
+def test_table1_single_disk_meets_paper_error(precision, tol):
+    """Table 1 (tests/golden/table1_single_disk.json): the HIP path on the paper's
+    single-disk problem, evaluated on the paper's full 200 x 200 grid of the 5 x 5
+    domain against eq. true_soln, is more accurate than every entry of the table."""
+    from test_oracle_pins import _table1, _true_soln, table1_targets
+    t = _table1()
+    best = min(min(t[k]["linf"]) for k in ("p4", "p6", "p8"))
+    pb = _problem(workloads.single_disk(1.0, 0.25), 20, 8, tol=tol, precision=precision)
+    pb.set_boundary_data(pb.boundary_label(yq.YQ_LABEL_JANUS, 2.0, 0.0))
+    sig, info = pb.solve()
+    assert info["residual"] <= tol and info["iterations"] <= 30
+    pts = table1_targets(1, 20)
+    u = _np(pb.eval_potential(sig, pts))
+    err = np.abs(u - _true_soln(pts, 0.25)).max()
+    assert err < best, (err, best)
