@@ -56,7 +56,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--kappa", type=float, default=1.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-rows", type=int, default=384)
+    ap.add_argument("--cpu-rows", type=int, default=1536)
     ap.add_argument("--fp64-steps", type=int, default=3)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy (counter calibration)")
@@ -157,12 +157,14 @@ def cpu_baseline(cfg, rows):
     from oracle.geometry import Params
     parts = cfg["particles"]
     d = oracle.discretize(parts, Params(panels=cfg["panels"], qbx_order=cfg["qbx_order"]))
+    from threadpoolctl import threadpool_limits
     sig = np.random.default_rng(0).standard_normal(d.N)
     sel = np.linspace(0, d.N - 1, rows).astype(int).tolist()
-    oracle.apply_rows(d, sel[:2], sig)   # warm-up
-    t0 = time.perf_counter()
-    oracle.apply_rows(d, sel, sig)
-    dt = time.perf_counter() - t0
+    with threadpool_limits(limits=1):    # one core, so "cores" below is exact
+        oracle.apply_rows(d, sel[:2], sig)   # warm-up
+        t0 = time.perf_counter()
+        oracle.apply_rows(d, sel, sig)
+        dt = time.perf_counter() - t0
     return dict(value=rows * d.N / dt, unit="interactions/s", cores=1, kind="oracle",
                 sample=f"{rows} of {d.N} operator rows of the same workload "
                        f"(each row: {d.N} far-field pairs + QBX window), single-threaded "

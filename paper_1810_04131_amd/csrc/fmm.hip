@@ -69,6 +69,31 @@ __device__ inline void iseries(double x, int n, double* I, int stride) {
   }
 }
 
+// Scaled modified Bessel functions of this lane, It_n = I_n(x) n! / (x/2)^n with
+// t = x^2/4, for n = 0..nmax, into col[n * 64] (the lane's LDS column): the two
+// highest orders by their ascending series, the others by the backward
+// recurrence It_{n-1} = It_n + t It_{n+1} / (n (n+1)), which follows from
+// I_{n-1} = I_{n+1} + (2n/x) I_n and adds positive terms only.
+__device__ inline void iscaled_col(double t, int nmax, double* col) {
+  auto ser = [t](int n) {
+    double term = 1.0, sum = 1.0;
+    for (int k = 1; k < 200; ++k) {
+      term *= t * rcp64(double(k) * double(n + k));
+      sum += term;
+      if (term <= 1e-17 * sum) break;
+    }
+    return sum;
+  };
+  double hi = ser(nmax + 1), cur = ser(nmax);
+  col[nmax * 64] = cur;
+  for (int n = nmax; n >= 1; --n) {
+    const double prev = fma(t * hi, rcp64(double(n) * double(n + 1)), cur);
+    col[(n - 1) * 64] = prev;
+    hi = cur;
+    cur = prev;
+  }
+}
+
 // Sum over the 64 lanes of a wave (fixed butterfly order: the same bits on every run).
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -173,10 +198,12 @@ __global__ __launch_bounds__(64) void p2m_kernel(int p, double kappa, const int*
                                                  const double* __restrict__ qx,
                                                  const double* __restrict__ qy,
                                                  double2* __restrict__ M) {
+  extern __shared__ double itab[];   // [(p + 2) * 64]: scaled I_n, one column per lane
   const int lane = threadIdx.x;
   const int b = blockIdx.x;
   const int s0 = ls[b], cnt = lc[b];
   const double cx = ccx[b], cy = ccy[b];
+  double* col = itab + lane;
   double2 mine = make_double2(0.0, 0.0);
   for (int r0 = 0; r0 < cnt; r0 += 64) {
     const int j = r0 + lane;
@@ -191,8 +218,9 @@ __global__ __launch_bounds__(64) void p2m_kernel(int p, double kappa, const int*
     const double x = kappa * rho, t = 0.25 * x * x, hx = 0.5 * x;
     const double2 e1 = rho > 0.0 ? make_double2(dx / rho, dy / rho) : make_double2(1.0, 0.0);
     const double2 Qc = cconj(Q);
+    iscaled_col(t, p + 1, col);
     double pref = hx;                               // (x/2)^{n+1} / (n+1)!
-    double Im = 0.0, I0 = iorder(t, 1.0, 0), Ip = iorder(t, pref, 1);
+    double Im = 0.0, I0 = col[0], Ip = pref * col[64];
     double2 Em = cconj(e1), Ep = e1;                // e^{i(n-1)phi}, e^{i(n+1)phi}
     for (int n = 0; n <= p; ++n) {
       const double2 gm = n == 0 ? make_double2(Ip * e1.x, Ip * e1.y)     // g_1
@@ -209,7 +237,7 @@ __global__ __launch_bounds__(64) void p2m_kernel(int p, double kappa, const int*
       pref *= hx * rcp64(double(n + 2));
       Im = I0;
       I0 = Ip;
-      Ip = iorder(t, pref, n + 2);
+      Ip = n + 2 <= p + 1 ? pref * col[(n + 2) * 64] : 0.0;   // I_{p+2} is never used
       Em = (n == 0) ? make_double2(1.0, 0.0) : cmul(Em, e1);
       Ep = cmul(Ep, e1);
     }
@@ -588,6 +616,7 @@ __global__ __launch_bounds__(FB) void l2p_p2p_kernel(int p, double kappa, int us
   double2* sxy = reinterpret_cast<double2*>(sh);            // [FB]
   double2* sq = sxy + FB;                                   // [FB] (FP64 strengths)
   float2* sq32 = reinterpret_cast<float2*>(sq + FB);        // [FB] (FP32 strengths)
+  double* col = reinterpret_cast<double*>(sq32 + FB) + threadIdx.x;   // [(p + 1) * 64] scaled I_n
   const int tid = threadIdx.x;
   const int b = blockIdx.x;
   const int s0 = ls[b], cnt = lc[b];
@@ -627,13 +656,14 @@ __global__ __launch_bounds__(FB) void l2p_p2p_kernel(int p, double kappa, int us
       const double x = kappa * rho, t = 0.25 * x * x, hx = 0.5 * x;
       const double2 e1 = rho > 0.0 ? make_double2(dx / rho, dy / rho) : make_double2(1.0, 0.0);
       const double2* lb = L + (int64_t)b * (p + 1);
-      loc = lb[0].x * iorder(t, 1.0, 0);
+      iscaled_col(t, p, col);
+      loc = lb[0].x * col[0];
       double2 E = e1;
       double pref = 1.0;                      // (x/2)^n / n!
       for (int n = 1; n <= p; ++n) {
         pref *= hx * rcp64(double(n));
         const double2 v = cmul(lb[n], E);
-        loc += 2.0 * v.x * iorder(t, pref, n);
+        loc += 2.0 * v.x * (pref * col[n * 64]);
         E = cmul(E, e1);
       }
     }
@@ -669,6 +699,7 @@ __global__ __launch_bounds__(FB) void l2p_p2p_grad_kernel(int p, double kappa,
   extern __shared__ double sh[];
   double2* sxy = reinterpret_cast<double2*>(sh);            // [FB]
   double2* sq = sxy + FB;                                   // [FB]
+  double* col = reinterpret_cast<double*>(sq + FB) + threadIdx.x;   // [(p + 2) * 64] scaled I_n
   const int tid = threadIdx.x;
   const int b = blockIdx.x;
   const int s0 = ls[b], cnt = lc[b];
@@ -699,15 +730,16 @@ __global__ __launch_bounds__(FB) void l2p_p2p_grad_kernel(int p, double kappa,
       const double x = kappa * rho, t = 0.25 * x * x, hx = 0.5 * x;
       const double2 e1 = rho > 0.0 ? make_double2(dx / rho, dy / rho) : make_double2(1.0, 0.0);
       const double2* lb = L + (int64_t)b * (p + 1);
+      iscaled_col(t, p + 1, col);
       double pref = hx;                                   // (x/2)^{n+1} / (n+1)!
-      double Iprev = iorder(t, 1.0, 0);                   // I_{n-1}
-      double Icur = iorder(t, pref, 1);                   // I_n
+      double Iprev = col[0];                              // I_{n-1}
+      double Icur = pref * col[64];                       // I_n
       double2 G = make_double2(lb[0].x * Icur * e1.x, lb[0].x * Icur * e1.y);
       double2 Eprev = make_double2(1.0, 0.0);             // e^{i(n-1) theta}
       double2 Enext = e1;                                 // e^{i(n+1) theta} after the update
       for (int n = 1; n <= p; ++n) {
         pref *= hx * rcp64(double(n + 1));
-        const double Inext = iorder(t, pref, n + 1);
+        const double Inext = pref * col[(n + 1) * 64];
         Enext = cmul(Enext, e1);
         const double2 a = cmul(lb[n], Enext);
         const double2 c = cconj(cmul(lb[n], Eprev));
@@ -1283,7 +1315,7 @@ void Fmm::expansions(const double* sigma, hipStream_t s, bool m2l32) {
   gather_kernel<<<(unsigned)((N + 255) / 256), 256, 0, s>>>(N, perm.p, sigma, wnxs.p, wnys.p, qx.p,
                                                             qy.p);
   FmmLevel& leaf = lv[depth];
-  p2m_kernel<<<leaf.nbox, 64, 0, s>>>(p, kappa, leaf_start.p, leaf_cnt.p, leaf.cx.p, leaf.cy.p, xs.p,
+  p2m_kernel<<<leaf.nbox, 64, (size_t)(p + 2) * 64 * sizeof(double), s>>>(p, kappa, leaf_start.p, leaf_cnt.p, leaf.cx.p, leaf.cy.p, xs.p,
                                       ys.p, qx.p, qy.p, leaf.M.p);
   for (int l = depth - 1; l >= 2; --l) {
     if (use_mfma) {
@@ -1325,7 +1357,8 @@ void Fmm::apply(const double* sigma, double* partial, bool p2p_fp32, const doubl
   // the FP32-class (inner) operator also takes its M2L in FP32 when that is set up
   expansions(sigma, s, p2p_fp32 && want_m2l32 && use_mfma);
   FmmLevel& leaf = lv[depth];
-  const size_t sh_l = (size_t)FB * (2 * sizeof(double2) + sizeof(float2));
+  const size_t sh_l =
+      (size_t)FB * (2 * sizeof(double2) + sizeof(float2)) + (size_t)(p + 1) * 64 * sizeof(double);
   if (p2p_fp32)
     l2p_p2p_kernel<true><<<leaf.nbox, FB, sh_l, s>>>(p, kappa, 1, leaf_start.p, leaf_cnt.p, nbp.p,
                                                      nbi.p, leaf.cx.p, leaf.cy.p, leaf.L.p, xs.p, ys.p,
@@ -1340,7 +1373,7 @@ void Fmm::apply(const double* sigma, double* partial, bool p2p_fp32, const doubl
 void Fmm::apply_grad(const double* sigma, double* gpart, const double* tab, hipStream_t s) {
   expansions(sigma, s);
   FmmLevel& leaf = lv[depth];
-  const size_t sh = (size_t)FB * 2 * sizeof(double2);
+  const size_t sh = (size_t)FB * 2 * sizeof(double2) + (size_t)(p + 2) * 64 * sizeof(double);
   l2p_p2p_grad_kernel<<<leaf.nbox, FB, sh, s>>>(p, kappa, leaf_start.p, leaf_cnt.p, nbp.p, nbi.p,
                                                  leaf.cx.p, leaf.cy.p, leaf.L.p, xs.p, ys.p, qx.p,
                                                  qy.p, perm.p, N, tab, gpart);

@@ -28,22 +28,31 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   return r;
 }
 
-// partial[k * nb + b] = sum over block b's rows of V[k][i] * w[i], k < kc
+// Sum over the block in a fixed order: a shuffle tree inside each wavefront, then
+// the four wavefront sums in order.  Valid in thread 0.
+__device__ __forceinline__ double block_sum_waves(double v, double* sh) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  return threadIdx.x == 0 ? ((sh[0] + sh[1]) + sh[2]) + sh[3] : 0.0;
+}
+
+// partial[k * nb + b] = sum over block b's rows of V[k][i] * w[i]; one block per
+// (row chunk b = blockIdx.x, column k = blockIdx.y), so small n still fills the GPU.
 __global__ __launch_bounds__(KB) void multidot_kernel(const double* __restrict__ V, int64_t ld,
                                                       int kc, const double* __restrict__ w,
                                                       int64_t n, double* __restrict__ partial) {
-  __shared__ double sh[KB];
+  __shared__ double sh[KB / 64];
   const int nb = gridDim.x;
+  const int k = blockIdx.y;
   const int64_t per = (n + nb - 1) / nb;
   const int64_t r0 = blockIdx.x * per;
   const int64_t r1 = min(n, r0 + per);
-  for (int k = 0; k < kc; ++k) {
-    const double* v = V + (int64_t)k * ld;
-    double acc = 0.0;
-    for (int64_t i = r0 + threadIdx.x; i < r1; i += KB) acc = fma(v[i], w[i], acc);
-    double s = block_sum(acc, sh);
-    if (threadIdx.x == 0) partial[(int64_t)k * nb + blockIdx.x] = s;
-  }
+  const double* v = V + (int64_t)k * ld;
+  double acc = 0.0;
+  for (int64_t i = r0 + threadIdx.x; i < r1; i += KB) acc = fma(v[i], w[i], acc);
+  const double s = block_sum_waves(acc, sh);
+  if (threadIdx.x == 0) partial[(int64_t)k * nb + blockIdx.x] = s;
 }
 
 // out[k] = sum_b partial[k * nb + b]
@@ -84,7 +93,8 @@ __global__ void scale_kernel(const double* __restrict__ x, const double* __restr
 
 void launch_multidot(const double* V, int64_t ld, int k, const double* w, int64_t n,
                      double* partial, int nb, hipStream_t s) {
-  multidot_kernel<<<nb, KB, 0, s>>>(V, ld, k, w, n, partial);
+  if (k < 1) return;
+  multidot_kernel<<<dim3(nb, k), KB, 0, s>>>(V, ld, k, w, n, partial);
   YQ_HIP(hipGetLastError());
 }
 
