@@ -35,12 +35,15 @@ sys.path.insert(0, ROOT)
 #         counted at this same figure): 2 differences, z^2 (3), rsq (1), Z (1),
 #         exp2 (1), rsq (1), degree-6 Horner (12), 3 products (3), D.q' (3),
 #         accumulate FMA (2)                                                   = 29
-#   FP64 (large-argument branch, which almost every pair takes): differences (2),
-#         r^2 (3), kappa^2 r^2 (1), two Newton-refined rsqrt (2 x 12), z (1), s (1),
-#         degree-20 Horner (40), e^-z by Cody-Waite + degree-13 Taylor (33),
-#         3 products (3), (x-y).q (3), product (1), accumulate (1)           = 113
+#   FP64, per (target group, source tile) class from the bounding circles: for
+#         kappa x gap >= 8 (72 % of the pairs of this workload at kappa = 1)
+#         differences (2), r^2 (3), kappa^2 r^2 (1), two Newton-refined rsqrt
+#         (2 x 12), z (1), s (1), degree-11 Horner (22), e^-z by Cody-Waite +
+#         degree-13 Taylor (33), 3 products (3), (x-y).q (3), product (1),
+#         accumulate (1) = 95; the other classes take the degree-15 or degree-20
+#         fit (103, 113) or the general form and are counted at the same 95
 F_DL32 = 29
-F_DL64 = 113
+F_DL64 = 95
 SRC_FOR_COUNTERS = ["paper_1810_04131_amd/csrc/farfield.hip",
                     "paper_1810_04131_amd/csrc/farfield_core.h", "paper_1810_04131_amd/csrc/bessel.h",
                     "paper_1810_04131_amd/csrc/bessel_tables.h"]

@@ -35,6 +35,7 @@
 namespace yq {
 
 constexpr int BB = 256;    // far-field block
+static_assert(BB == FT, "one source tile per staged block");
 constexpr int KR = 4096;   // rows per Krylov reduction block
 constexpr int KB2 = 256;   // Krylov block size
 
@@ -50,6 +51,7 @@ __global__ __launch_bounds__(BB) void bfar64_kernel(const ConfDev* __restrict__ 
                                                     const double* __restrict__ tab) {
   __shared__ double2 sxy[BB];
   __shared__ double2 sq[BB];
+  const int wib = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / FG));
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     const int4 w = items[it];
     const int c = w.x;
@@ -62,6 +64,8 @@ __global__ __launch_bounds__(BB) void bfar64_kernel(const ConfDev* __restrict__ 
     const double yi = i < N ? cd.y[i] : 0.0;
     const int64_t j0 = (int64_t)w.z * cd.chunk;
     const int64_t j1 = min(N, j0 + cd.chunk);
+    const int64_t grp = (int64_t)w.y * (BB / FG) + wib;
+    const bool live = grp * FG < N;
     double acc = 0.0;
     for (int64_t jb = j0; jb < j1; jb += BB) {
       const int64_t j = jb + threadIdx.x;
@@ -73,7 +77,9 @@ __global__ __launch_bounds__(BB) void bfar64_kernel(const ConfDev* __restrict__ 
       }
       __syncthreads();
       const int nb = (int)min((int64_t)BB, j1 - jb);
-      acc = far64_tile(xi, yi, sxy, sq, nb, cd.kap2, tab, acc);
+      const int cls = live ? far64_class(cd.f32.grp, cd.f32.tile, grp, jb / FT, cd.kappa)
+                           : C64_GENERAL;
+      acc = far64_class_tile(cls, xi, yi, sxy, sq, nb, cd.kap2, tab, acc);
     }
     if (i < N) cd.part64[(int64_t)w.z * N + i] = acc;
   }

@@ -22,7 +22,7 @@ namespace yq {
 // with a scalar operand.  (Literal 64-bit constants cannot be FMA operands
 // and cost a vector move per use.)
 constexpr int T_E = 0, T_F = 12, T_I0 = 24, T_P0 = 36, T_H0 = 48, T_H1 = 69, T_EX = 90,
-              T_SIZE = 104;
+              T_H0_Z8 = 104, T_H1_Z8 = 116, T_H0_Z4 = 128, T_H1_Z4 = 144, T_SIZE = 160;
 static_assert(T_SIZE == T_SIZE_HOST, "table size");
 
 // e^-r = sum_k (-r)^k / k!, k = 0..13, for |r| <= ln2/2 (truncation < 4e-18)
@@ -36,6 +36,14 @@ inline void build_tab64(double* t) {
   for (int k = 0; k < 21; ++k) {
     t[T_H0 + k] = kH0_64[k];
     t[T_H1 + k] = kH1_64[k];
+  }
+  for (int k = 0; k < 12; ++k) {
+    t[T_H0_Z8 + k] = kH0_64_z8[k];
+    t[T_H1_Z8 + k] = kH1_64_z8[k];
+  }
+  for (int k = 0; k < 16; ++k) {
+    t[T_H0_Z4 + k] = kH0_64_z4[k];
+    t[T_H1_Z4 + k] = kH1_64_z4[k];
   }
   double f = 1.0;
   for (int k = 0; k < 14; ++k) {
@@ -111,6 +119,28 @@ __device__ __forceinline__ double k1z_64(double z2, const double* __restrict__ T
   double z = z2 * y;
   double q = rsqrt64(z);   // z^(-1/2)
   return hornerT<21>(T + T_H1, 2.0 * y) * expm64(z, T) * q * y;
+}
+
+// Large-argument forms for pairs whose z is known to be at least 2, 4 or 8: h_n
+// from the degree-(NC - 1) fit stored at T + H0 / T + H1 (a fit for that range).
+template <int NC, int H1>
+__device__ __forceinline__ double k1z_64_large(double z2, const double* __restrict__ T) {
+  double y = rsqrt64(z2);  // 1/z
+  double z = z2 * y;
+  double q = rsqrt64(z);   // z^(-1/2)
+  return hornerT<NC>(T + H1, 2.0 * y) * expm64(z, T) * q * y;
+}
+
+template <int NC, int H0, int H1>
+__device__ __forceinline__ void k0_k1z_64_large(double z2, double& k0, double& k1z,
+                                                const double* __restrict__ T) {
+  double y = rsqrt64(z2);
+  double z = z2 * y;
+  double q = rsqrt64(z);
+  double e = expm64(z, T) * q;
+  double s = 2.0 * y;
+  k0 = hornerT<NC>(T + H0, s) * e;
+  k1z = hornerT<NC>(T + H1, s) * e * y;
 }
 
 // K0(z) and K1(z)/z together for z^2 = z2.

@@ -20,7 +20,7 @@ constexpr int MAXP_FMM = 48;     // largest FMM order
 constexpr int64_t kFmmAutoNodes = 20000;
 constexpr int MAXSUB = 16;       // largest oversampling factor
 constexpr double PI = 3.14159265358979323846264338327950288;
-constexpr int T_SIZE_HOST = 104;  // doubles in the FP64 coefficient table (bessel.h T_SIZE)
+constexpr int T_SIZE_HOST = 160;  // doubles in the FP64 coefficient table (bessel.h T_SIZE)
 
 struct Error {
   int code;
@@ -140,6 +140,8 @@ struct GeomView {
   const double* wny;     // w * ny
   const double* panel_h; // [n*P]
   const double* tab;     // FP64 special-function coefficients (bessel.h, T_SIZE doubles)
+  const double4* ftile;  // bounding circles of 256-node source tiles
+  const double4* fgrp;   // bounding circles of 64-node target groups
 };
 
 // Discretisation constants, passed to kernels by value.

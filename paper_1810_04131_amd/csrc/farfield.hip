@@ -18,6 +18,7 @@
 namespace yq {
 
 constexpr int FAR_BS = 256;
+static_assert(FAR_BS == FT, "FP64 kernels stage one source tile per block iteration");
 
 // Source chunks are chosen so that one configuration alone gives about `want`
 // blocks (>= 16 per compute unit at 4096); the plan depends only on the sizes.
@@ -46,6 +47,10 @@ __global__ __launch_bounds__(FAR_BS) void far64_kernel(GeomView g, const double*
   const double kap2 = g.kappa * g.kappa;
   const int64_t j0 = (int64_t)blockIdx.y * chunk;
   const int64_t j1 = min(N, j0 + chunk);
+  // target group of this wavefront (whole wavefronts past N keep the general form)
+  const int64_t grp = blockIdx.x * (int64_t)(FAR_BS / FG) +
+                      __builtin_amdgcn_readfirstlane((int)(threadIdx.x / FG));
+  const bool live = grp * FG < N;
   double acc = 0.0;
   for (int64_t jb = j0; jb < j1; jb += FAR_BS) {
     const int64_t j = jb + threadIdx.x;
@@ -57,7 +62,8 @@ __global__ __launch_bounds__(FAR_BS) void far64_kernel(GeomView g, const double*
     }
     __syncthreads();
     const int nb = (int)min((int64_t)FAR_BS, j1 - jb);
-    acc = far64_tile(xi, yi, sxy, sq, nb, kap2, g.tab, acc);
+    const int cls = live ? far64_class(g.fgrp, g.ftile, grp, jb / FT, g.kappa) : C64_GENERAL;
+    acc = far64_class_tile(cls, xi, yi, sxy, sq, nb, kap2, g.tab, acc);
   }
   if (i < N) partial[(int64_t)blockIdx.y * N + i] = acc;
 }
@@ -138,6 +144,9 @@ __global__ __launch_bounds__(FAR_BS) void far_grad64_kernel(GeomView g,
   const double kap2 = g.kappa * g.kappa;
   const int64_t j0 = (int64_t)blockIdx.y * chunk;
   const int64_t j1 = min(N, j0 + chunk);
+  const int64_t grp = blockIdx.x * (int64_t)(FAR_BS / FG) +
+                      __builtin_amdgcn_readfirstlane((int)(threadIdx.x / FG));
+  const bool live = grp * FG < N;
   double ax = 0.0, ay = 0.0;
   for (int64_t jb = j0; jb < j1; jb += FAR_BS) {
     const int64_t j = jb + threadIdx.x;
@@ -149,7 +158,8 @@ __global__ __launch_bounds__(FAR_BS) void far_grad64_kernel(GeomView g,
     }
     __syncthreads();
     const int nb = (int)min((int64_t)FAR_BS, j1 - jb);
-    far_grad64_tile(xi, yi, sxy, sq, nb, kap2, g.tab, ax, ay);
+    const int cls = live ? far64_class(g.fgrp, g.ftile, grp, jb / FT, g.kappa) : C64_GENERAL;
+    far_grad64_class_tile(cls, xi, yi, sxy, sq, nb, kap2, g.tab, ax, ay);
   }
   if (i < N) {
     partial[((int64_t)blockIdx.y * 2 + 0) * N + i] = ax;

@@ -23,6 +23,44 @@ __device__ __forceinline__ double far64_tile(double xi, double yi, const double2
   return acc;
 }
 
+// ---- FP64 far field: tile classes -------------------------------------------------------
+//
+// The smallest z of a (target group, source tile) pair, from their bounding
+// circles, picks the evaluation of all its pairs: z >= 8 and z >= 4 take short
+// fits of h_n (s <= 1/4 and 1/2), z >= 2 the full large-argument fit, and only
+// pairs whose z may be smaller (the self pair included) take the general form
+// with both branches.  The class is the same for every lane of a wavefront.
+constexpr int C64_GENERAL = 0, C64_Z2 = 1, C64_Z4 = 2, C64_Z8 = 3;
+
+__device__ __forceinline__ int far64_class(const double4* grp, const double4* tile, int64_t g,
+                                           int64_t t, double kappa);
+
+template <int NC, int H1>
+__device__ __forceinline__ double far64_far_tile(double xi, double yi, const double2* sxy,
+                                                 const double2* sq, int nb, double kap2,
+                                                 const double* __restrict__ tab, double acc) {
+  for (int k = 0; k < nb; ++k) {
+    const double2 p = sxy[k];
+    const double2 q = sq[k];
+    const double dx = xi - p.x, dy = yi - p.y;
+    const double r2 = fma(dx, dx, dy * dy);
+    acc += k1z_64_large<NC, H1>(kap2 * r2, tab) * fma(dx, q.x, dy * q.y);
+  }
+  return acc;
+}
+
+__device__ __forceinline__ double far64_class_tile(int cls, double xi, double yi,
+                                                   const double2* sxy, const double2* sq, int nb,
+                                                   double kap2, const double* __restrict__ tab,
+                                                   double acc) {
+  switch (cls) {
+    case C64_Z8: return far64_far_tile<12, T_H1_Z8>(xi, yi, sxy, sq, nb, kap2, tab, acc);
+    case C64_Z4: return far64_far_tile<16, T_H1_Z4>(xi, yi, sxy, sq, nb, kap2, tab, acc);
+    case C64_Z2: return far64_far_tile<21, T_H1>(xi, yi, sxy, sq, nb, kap2, tab, acc);
+    default: return far64_tile(xi, yi, sxy, sq, nb, kap2, tab, acc);
+  }
+}
+
 // FP32 over an LDS-staged tile (FMM neighbour interactions); positions stay
 // FP64 and the difference is rounded to FP32.
 __device__ __forceinline__ float far32_tile(double xi, double yi, const double2* sxy,
@@ -141,6 +179,15 @@ __device__ __forceinline__ float far32_range(const Far32View& v, int64_t i, int6
   return fmaf(accn, v.nscale, accf);
 }
 
+__device__ __forceinline__ int far64_class(const double4* grp, const double4* tile, int64_t g,
+                                           int64_t t, double kappa) {
+  kptr<double> gc = as_k((const double*)grp) + 4 * g;
+  kptr<double> tc = as_k((const double*)tile) + 4 * t;
+  const double cx = gc[0] - tc[0], cy = gc[1] - tc[1];
+  const double zmin = kappa * (sqrt(cx * cx + cy * cy) - gc[2] - tc[2]);
+  return zmin >= 8.0 ? C64_Z8 : zmin >= 4.0 ? C64_Z4 : zmin >= 2.0 ? C64_Z2 : C64_GENERAL;
+}
+
 // Gradient of the double layer over a staged source tile, accumulated into
 // (ax, ay) in the scaling of far64_tile:
 // (K1(z)/z) q - ((x-y).q) (x-y) (K0(z) + 2 K1(z)/z) / r^2, self pair skipped.
@@ -161,6 +208,46 @@ __device__ __forceinline__ void far_grad64_tile(double xi, double yi, const doub
       ax += k1z * q.x - b * dx;
       ay += k1z * q.y - b * dy;
     }
+  }
+}
+
+// Gradient pairs of a tile whose z is at least 2 (4, 8): no self pair, large branch only.
+template <int NC, int H0, int H1>
+__device__ __forceinline__ void far_grad64_far_tile(double xi, double yi, const double2* sxy,
+                                                    const double2* sq, int nb, double kap2,
+                                                    const double* __restrict__ tab, double& ax,
+                                                    double& ay) {
+  for (int k = 0; k < nb; ++k) {
+    const double2 p = sxy[k];
+    const double2 q = sq[k];
+    const double dx = xi - p.x, dy = yi - p.y;
+    const double r2 = fma(dx, dx, dy * dy);
+    double k0, k1z;
+    k0_k1z_64_large<NC, H0, H1>(kap2 * r2, k0, k1z, tab);
+    const double dq = fma(dx, q.x, dy * q.y);
+    const double b = dq * (k0 + 2.0 * k1z) * rcp64(r2);
+    ax += k1z * q.x - b * dx;
+    ay += k1z * q.y - b * dy;
+  }
+}
+
+__device__ __forceinline__ void far_grad64_class_tile(int cls, double xi, double yi,
+                                                      const double2* sxy, const double2* sq,
+                                                      int nb, double kap2,
+                                                      const double* __restrict__ tab, double& ax,
+                                                      double& ay) {
+  switch (cls) {
+    case C64_Z8:
+      far_grad64_far_tile<12, T_H0_Z8, T_H1_Z8>(xi, yi, sxy, sq, nb, kap2, tab, ax, ay);
+      break;
+    case C64_Z4:
+      far_grad64_far_tile<16, T_H0_Z4, T_H1_Z4>(xi, yi, sxy, sq, nb, kap2, tab, ax, ay);
+      break;
+    case C64_Z2:
+      far_grad64_far_tile<21, T_H0, T_H1>(xi, yi, sxy, sq, nb, kap2, tab, ax, ay);
+      break;
+    default:
+      far_grad64_tile(xi, yi, sxy, sq, nb, kap2, tab, ax, ay);
   }
 }
 

@@ -111,6 +111,8 @@ struct yq_problem {
     g.wny = wny.p;
     g.panel_h = panel_h.p;
     g.tab = tab.p;
+    g.ftile = ftile.p;
+    g.fgrp = fgrp.p;
     return g;
   }
 };
