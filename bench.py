@@ -28,22 +28,55 @@ sys.path.insert(0, ROOT)
 
 # Algorithmic flops per source-target pair of the far-field kernels, counted
 # from the source: an FMA counts 2, every other floating-point arithmetic
-# operation (add, mul, rsq, exp2, rint, ldexp) counts 1.
-#   FP32, far path (every pair of a target group / source tile pair whose
-#         circles are at least 2 / kappa apart: 95 % of the pairs of this
-#         workload; the other 5 % take the general path, which costs more and is
-#         counted at this same figure): 2 differences, z^2 (3), rsq (1), Z (1),
-#         exp2 (1), rsq (1), degree-6 Horner (12), 3 products (3), D.q' (3),
-#         accumulate FMA (2)                                                   = 29
-#   FP64, per (target group, source tile) class from the bounding circles: for
-#         kappa x gap >= 8 (72 % of the pairs of this workload at kappa = 1)
-#         differences (2), r^2 (3), kappa^2 r^2 (1), two Newton-refined rsqrt
-#         (2 x 12), z (1), s (1), degree-11 Horner (22), e^-z by Cody-Waite +
-#         degree-13 Taylor (33), 3 products (3), (x-y).q (3), product (1),
-#         accumulate (1) = 95; the other classes take the degree-15 or degree-20
-#         fit (103, 113) or the general form and are counted at the same 95
-F_DL32 = 29
-F_DL64 = 95
+# operation (add, mul, rsq, exp2, log2, rcp, rint, ldexp) counts 1.  A pair's
+# evaluation depends on the class of its (64-node target group, 256-node source
+# tile) pair, kappa x (gap between their bounding circles):
+#   FP32  >= 8: 2 differences, z^2 (3), rsq (1), Z (1), exp2 (1), rsq (1),
+#               degree-3 Horner (6), 3 products (3), D.q' (3), accumulate (2) = 23
+#         >= 4: the same with the degree-4 Horner (8)                          = 25
+#         >= 2: the same with the degree-6 Horner (12)                         = 29
+#         general (may be < 2): FP64 differences (2), z^2 (3), kappa^2 z^2 (1),
+#               large branch rsq, z, exp2 argument + exp2, rsq, degree-6 Horner,
+#               3 products (20), (x-y).q (3), accumulate (2); counted at the
+#               cheaper branch                                                  = 31
+#   FP64  >= 8: differences (2), r^2 (3), kappa^2 r^2 (1), two Newton-refined
+#               rsqrt (2 x 12), z (1), s (1), degree-11 Horner (22), e^-z by
+#               Cody-Waite + degree-13 Taylor (33), 3 products (3), (x-y).q (3),
+#               product (1), accumulate (1)                                     = 95
+#         >= 4: degree-15 Horner (30)                                          = 103
+#         >= 2 and general: degree-20 Horner (40)                              = 113
+F32_CLASS = {"z8": 23, "z4": 25, "z2": 29, "general": 31}
+F64_CLASS = {"z8": 95, "z4": 103, "z2": 113, "general": 113}
+
+
+def far_class_mix(x, y, kappa):
+    """Fraction of the N^2 far-field pairs in each kernel class, from the same
+    bounding circles as the kernels (bounding-box centre, largest distance)."""
+    import numpy as np
+    n = len(x)
+
+    def circles(g):
+        out = []
+        for a in range(0, n, g):
+            px, py = x[a:a + g], y[a:a + g]
+            cx, cy = 0.5 * (px.min() + px.max()), 0.5 * (py.min() + py.max())
+            out.append((cx, cy, np.sqrt(((px - cx) ** 2 + (py - cy) ** 2).max()), len(px)))
+        return np.array(out)
+
+    t, g = circles(256), circles(64)
+    zmin = kappa * (np.hypot(g[:, None, 0] - t[None, :, 0], g[:, None, 1] - t[None, :, 1])
+                    - g[:, None, 2] - t[None, :, 2])
+    w = g[:, None, 3] * t[None, :, 3]
+    tot = w.sum()
+    masks = {"z8": zmin >= 8, "z4": (zmin >= 4) & (zmin < 8), "z2": (zmin >= 2) & (zmin < 4),
+             "general": zmin < 2}
+    return {c: float(w[m].sum() / tot) for c, m in masks.items()}
+
+
+def flops_per_pair(mix, table):
+    return sum(mix[c] * table[c] for c in table)
+
+
 SRC_FOR_COUNTERS = ["paper_1810_04131_amd/csrc/farfield.hip",
                     "paper_1810_04131_amd/csrc/farfield_core.h", "paper_1810_04131_amd/csrc/bessel.h",
                     "paper_1810_04131_amd/csrc/bessel_tables.h"]
@@ -513,7 +546,11 @@ def main():
     avg32 = ms32 / max(n32, 1) * 1e-3
     avg64 = ms64 / max(n64, 1) * 1e-3
     pairs = float(N) * (N - 1)
-    achieved32 = F_DL32 * pairs / avg32
+    nd = pb.nodes()
+    mix = far_class_mix(nd["x"].cpu().numpy(), nd["y"].cpu().numpy(), args.kappa)
+    f32_pair = flops_per_pair(mix, F32_CLASS)
+    f64_pair = flops_per_pair(mix, F64_CLASS)
+    achieved32 = f32_pair * pairs / avg32
     ms_step = t_all / args.steps * 1e3
 
     # FP64-only path on the same workload (the reference for solve latency)
@@ -567,11 +604,13 @@ def main():
         "fp64_path": {"latency_ms_p50": percentile(lat64, 0.5) * 1e3,
                       "solves_per_s": 1.0 / max(percentile(lat64, 0.5), 1e-12),
                       "gmres_iterations": it64[-1] if it64 else None,
-                      "far64_achieved_tflops": F_DL64 * pairs / avg64b / 1e12 if n64b else None,
-                      "far64_frac_of_fp64_peak": F_DL64 * pairs / avg64b / PEAK_FP64 if n64b else None},
+                      "far64_achieved_tflops": f64_pair * pairs / avg64b / 1e12 if n64b else None,
+                      "far64_frac_of_fp64_peak": f64_pair * pairs / avg64b / PEAK_FP64 if n64b else None,
+                      "far64_flops_per_pair": f64_pair},
         "roofline": {"bound": "alu", "kernel": "far32_kernel", "achieved": achieved32 / 1e12,
                      "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s", "frac": achieved32 / PEAK_FP32,
-                     "traffic": traffic_from_counters(pairs), "flops_per_pair": F_DL32,
+                     "traffic": traffic_from_counters(pairs), "flops_per_pair": f32_pair,
+                     "pair_classes": mix,
                      "source_sha256_16": source_hash(),
                      "pairs_per_launch": pairs, "avg_launch_ms": avg32 * 1e3},
     }

@@ -197,7 +197,7 @@ struct Far32View {
   const float4* src;   // per node, packed per matvec
   int64_t N;
   double s;            // kappa log2(e)
-  double dfar;         // far when the gap between circles is >= 2 / kappa
+  double kappa;        // pairs are far when kappa x the gap between circles is >= 2
   double qc;           // sqrt(log2 e) / kappa: source strength scaling of the records
   float kap2;          // kappa^2 (general path)
   float nscale;        // kappa / sqrt(log2 e): general-path sum -> far-path scaling

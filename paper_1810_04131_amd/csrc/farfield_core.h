@@ -98,7 +98,9 @@ __device__ __forceinline__ kptr<T> as_k(const T* p) {
 
 
 // Far pairs: with D = s (x_i - y_j), Z2 = |D|^2 = (z log2 e)^2, Y = 1/sqrt(Z2),
-// K1(z)/z ((x_i - y_j) . q) = 2^-Z h1(2 log2(e) Y) (Y / sqrt(Z)) (D . q').
+// K1(z)/z ((x_i - y_j) . q) = 2^-Z h1(2 log2(e) Y) (Y / sqrt(Z)) (D . q').  H is
+// the fit of h1 for the tile's range of z (z >= 2, 4 or 8), as a polynomial in Y.
+template <int NH, const float (&H)[NH]>
 __device__ __forceinline__ float far32_pair(float tx, float ty, float4 p, float acc) {
   const float dx = tx - p.x, dy = ty - p.y;
   const float z2 = fmaf(dx, dx, dy * dy);
@@ -106,7 +108,7 @@ __device__ __forceinline__ float far32_pair(float tx, float ty, float4 p, float 
   const float z = z2 * yv;
   const float e = __builtin_amdgcn_exp2f(-z);
   const float q = __builtin_amdgcn_rsqf(z);
-  const float h = horner(kH1Y_32, yv);
+  const float h = horner(H, yv);
   return fmaf((e * h) * (q * yv), fmaf(dx, p.z, dy * p.w), acc);
 }
 
@@ -116,16 +118,17 @@ __device__ __forceinline__ float4 ld_rec(kptr<float> p) {
 
 // sp: the tile's records as 4 floats each; nb a multiple of 16 (panels hold 16
 // nodes).  The next 4 records are loaded (scalar) before the current 4 are used.
+template <int NH, const float (&H)[NH]>
 __device__ __forceinline__ float far32_far_tile(float tx, float ty, kptr<float> sp, int nb,
                                                 float acc) {
   float4 a0 = ld_rec(sp), a1 = ld_rec(sp + 4), a2 = ld_rec(sp + 8), a3 = ld_rec(sp + 12);
   for (int k = 0; k < nb; k += 4) {
     kptr<float> pn = sp + 4 * (k + 4 < nb ? k + 4 : k);
     const float4 b0 = ld_rec(pn), b1 = ld_rec(pn + 4), b2 = ld_rec(pn + 8), b3 = ld_rec(pn + 12);
-    acc = far32_pair(tx, ty, a0, acc);
-    acc = far32_pair(tx, ty, a1, acc);
-    acc = far32_pair(tx, ty, a2, acc);
-    acc = far32_pair(tx, ty, a3, acc);
+    acc = far32_pair<NH, H>(tx, ty, a0, acc);
+    acc = far32_pair<NH, H>(tx, ty, a1, acc);
+    acc = far32_pair<NH, H>(tx, ty, a2, acc);
+    acc = far32_pair<NH, H>(tx, ty, a3, acc);
     a0 = b0;
     a1 = b1;
     a2 = b2;
@@ -140,13 +143,35 @@ __device__ __forceinline__ float far32_far_tile(float tx, float ty, kptr<float> 
 __device__ __forceinline__ float far32_near_tile(double xi, double yi, kptr<double> sx,
                                                  kptr<double> sy, kptr<float> sp, int nb,
                                                  float kap2, float acc) {
-  for (int k = 0; k < nb; k += 4) {
+  // four sources at a time; the next four are loaded (scalar) before these are used
+  double ax[4], ay[4];
+  float aqx[4], aqy[4];
+  auto load = [&](int k, double* x, double* y, float* qx, float* qy) {
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      kptr<float> p = sp + 4 * (k + u);
-      const float dx = (float)(xi - sx[k + u]), dy = (float)(yi - sy[k + u]);
+      x[u] = sx[k + u];
+      y[u] = sy[k + u];
+      qx[u] = sp[4 * (k + u) + 2];
+      qy[u] = sp[4 * (k + u) + 3];
+    }
+  };
+  load(0, ax, ay, aqx, aqy);
+  for (int k = 0; k < nb; k += 4) {
+    double bx[4], by[4];
+    float bqx[4], bqy[4];
+    load(k + 4 < nb ? k + 4 : k, bx, by, bqx, bqy);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const float dx = (float)(xi - ax[u]), dy = (float)(yi - ay[u]);
       const float z2 = fmaxf(kap2 * fmaf(dx, dx, dy * dy), 1e-30f);
-      acc = fmaf(k1z_32(z2), fmaf(dx, p[2], dy * p[3]), acc);
+      acc = fmaf(k1z_32(z2), fmaf(dx, aqx[u], dy * aqy[u]), acc);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      ax[u] = bx[u];
+      ay[u] = by[u];
+      aqx[u] = bqx[u];
+      aqy[u] = bqy[u];
     }
   }
   return acc;
@@ -166,11 +191,16 @@ __device__ __forceinline__ float far32_range(const Far32View& v, int64_t i, int6
     kptr<double> tc = as_k((const double*)v.tile) + 4 * (jb / FT);
     const double tcx = tc[0], tcy = tc[1];
     const double cx = gx - tcx, cy = gy - tcy;
-    const double gap = sqrt(cx * cx + cy * cy) - gr - tc[2];
+    const double zmin = v.kappa * (sqrt(cx * cx + cy * cy) - gr - tc[2]);
     const int nb = (int)min((int64_t)FT, j1 - jb);
-    if (gap >= v.dfar) {
+    if (zmin >= 2.0) {
       const float tx = (float)((xi - tcx) * v.s), ty = (float)((yi - tcy) * v.s);
-      accf = far32_far_tile(tx, ty, src + 4 * jb, nb, accf);
+      if (zmin >= 8.0)
+        accf = far32_far_tile<4, kH1Y_32_z8>(tx, ty, src + 4 * jb, nb, accf);
+      else if (zmin >= 4.0)
+        accf = far32_far_tile<5, kH1Y_32_z4>(tx, ty, src + 4 * jb, nb, accf);
+      else
+        accf = far32_far_tile<7, kH1Y_32>(tx, ty, src + 4 * jb, nb, accf);
     } else {
       accn = far32_near_tile(xi, yi, as_k(v.x) + jb, as_k(v.y) + jb, src + 4 * jb, nb, v.kap2,
                              accn);

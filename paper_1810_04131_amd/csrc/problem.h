@@ -83,7 +83,7 @@ struct yq_problem {
     v.src = fsrc.p;
     v.N = N;
     v.s = kappa * LOG2E;
-    v.dfar = 2.0 / kappa;
+    v.kappa = kappa;
     v.qc = SQRT_LOG2E / kappa;   // the same expression as in pack32
     v.kap2 = (float)(kappa * kappa);
     v.nscale = (float)(kappa / SQRT_LOG2E);
