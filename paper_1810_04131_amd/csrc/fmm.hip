@@ -69,6 +69,11 @@ __device__ inline void iseries(double x, int n, double* I, int stride) {
   }
 }
 
+// Orders up to this keep the scaled I_n of each lane in LDS (iscaled_col); above
+// it the column would cut the leaf kernels' occupancy by more than the recurrence
+// saves, and each I_n comes from its own series (iorder).
+constexpr int kColMaxOrder = 24;
+
 // Scaled modified Bessel functions of this lane, It_n = I_n(x) n! / (x/2)^n with
 // t = x^2/4, for n = 0..nmax, into col[n * 64] (the lane's LDS column): the two
 // highest orders by their ascending series, the others by the backward
@@ -189,7 +194,8 @@ constexpr int FB = 64;
 // One wave per leaf: multipole coefficients M_n, n = 0..p.  A lane takes one
 // node at a time, rolls I_{n-1}, I_n, I_{n+1} and e^{i(n +- 1) phi} along n, and
 // the wave sums each coefficient; lane n keeps M_n.
-__global__ __launch_bounds__(64) void p2m_kernel(int p, double kappa, const int* __restrict__ ls,
+__global__ __launch_bounds__(64) void p2m_kernel(int p, int use_col, double kappa,
+                                                 const int* __restrict__ ls,
                                                  const int* __restrict__ lc,
                                                  const double* __restrict__ ccx,
                                                  const double* __restrict__ ccy,
@@ -218,9 +224,10 @@ __global__ __launch_bounds__(64) void p2m_kernel(int p, double kappa, const int*
     const double x = kappa * rho, t = 0.25 * x * x, hx = 0.5 * x;
     const double2 e1 = rho > 0.0 ? make_double2(dx / rho, dy / rho) : make_double2(1.0, 0.0);
     const double2 Qc = cconj(Q);
-    iscaled_col(t, p + 1, col);
+    if (use_col) iscaled_col(t, p + 1, col);
     double pref = hx;                               // (x/2)^{n+1} / (n+1)!
-    double Im = 0.0, I0 = col[0], Ip = pref * col[64];
+    double Im = 0.0, I0 = use_col ? col[0] : iorder(t, 1.0, 0);
+    double Ip = use_col ? pref * col[64] : iorder(t, pref, 1);
     double2 Em = cconj(e1), Ep = e1;                // e^{i(n-1)phi}, e^{i(n+1)phi}
     for (int n = 0; n <= p; ++n) {
       const double2 gm = n == 0 ? make_double2(Ip * e1.x, Ip * e1.y)     // g_1
@@ -237,7 +244,8 @@ __global__ __launch_bounds__(64) void p2m_kernel(int p, double kappa, const int*
       pref *= hx * rcp64(double(n + 2));
       Im = I0;
       I0 = Ip;
-      Ip = n + 2 <= p + 1 ? pref * col[(n + 2) * 64] : 0.0;   // I_{p+2} is never used
+      Ip = n + 2 > p + 1 ? 0.0                                 // I_{p+2} is never used
+                         : (use_col ? pref * col[(n + 2) * 64] : iorder(t, pref, n + 2));
       Em = (n == 0) ? make_double2(1.0, 0.0) : cmul(Em, e1);
       Ep = cmul(Ep, e1);
     }
@@ -597,7 +605,7 @@ __global__ void l2l_kernel(int p, int nbox, const int* __restrict__ parent, cons
 // interactions with the 3 x 3 neighbourhood; writes partial[node] in the far-field
 // kernels' scaling (far field * 2 pi / kappa^2).
 template <bool F32>
-__global__ __launch_bounds__(FB) void l2p_p2p_kernel(int p, double kappa, int use_local,
+__global__ __launch_bounds__(FB) void l2p_p2p_kernel(int p, double kappa, int use_local, int use_col,
                                                      const int* __restrict__ ls,
                                                      const int* __restrict__ lc,
                                                      const int* __restrict__ nbp,
@@ -656,14 +664,14 @@ __global__ __launch_bounds__(FB) void l2p_p2p_kernel(int p, double kappa, int us
       const double x = kappa * rho, t = 0.25 * x * x, hx = 0.5 * x;
       const double2 e1 = rho > 0.0 ? make_double2(dx / rho, dy / rho) : make_double2(1.0, 0.0);
       const double2* lb = L + (int64_t)b * (p + 1);
-      iscaled_col(t, p, col);
-      loc = lb[0].x * col[0];
+      if (use_col) iscaled_col(t, p, col);
+      loc = lb[0].x * (use_col ? col[0] : iorder(t, 1.0, 0));
       double2 E = e1;
       double pref = 1.0;                      // (x/2)^n / n!
       for (int n = 1; n <= p; ++n) {
         pref *= hx * rcp64(double(n));
         const double2 v = cmul(lb[n], E);
-        loc += 2.0 * v.x * (pref * col[n * 64]);
+        loc += 2.0 * v.x * (use_col ? pref * col[n * 64] : iorder(t, pref, n));
         E = cmul(E, e1);
       }
     }
@@ -681,7 +689,7 @@ __global__ __launch_bounds__(FB) void l2p_p2p_kernel(int p, double kappa, int us
 // since (d/dx + i d/dy) I_n(kappa rho) e^{i n theta} = kappa I_{n+1} e^{i(n+1) theta} for
 // every integer n (I_{-n} = I_n).  Writes gpart[node] (x) and gpart[N + node] (y) in
 // the gradient far-field kernels' scaling.
-__global__ __launch_bounds__(FB) void l2p_p2p_grad_kernel(int p, double kappa,
+__global__ __launch_bounds__(FB) void l2p_p2p_grad_kernel(int p, int use_col, double kappa,
                                                           const int* __restrict__ ls,
                                                           const int* __restrict__ lc,
                                                           const int* __restrict__ nbp,
@@ -730,16 +738,16 @@ __global__ __launch_bounds__(FB) void l2p_p2p_grad_kernel(int p, double kappa,
       const double x = kappa * rho, t = 0.25 * x * x, hx = 0.5 * x;
       const double2 e1 = rho > 0.0 ? make_double2(dx / rho, dy / rho) : make_double2(1.0, 0.0);
       const double2* lb = L + (int64_t)b * (p + 1);
-      iscaled_col(t, p + 1, col);
+      if (use_col) iscaled_col(t, p + 1, col);
       double pref = hx;                                   // (x/2)^{n+1} / (n+1)!
-      double Iprev = col[0];                              // I_{n-1}
-      double Icur = pref * col[64];                       // I_n
+      double Iprev = use_col ? col[0] : iorder(t, 1.0, 0);        // I_{n-1}
+      double Icur = use_col ? pref * col[64] : iorder(t, pref, 1);  // I_n
       double2 G = make_double2(lb[0].x * Icur * e1.x, lb[0].x * Icur * e1.y);
       double2 Eprev = make_double2(1.0, 0.0);             // e^{i(n-1) theta}
       double2 Enext = e1;                                 // e^{i(n+1) theta} after the update
       for (int n = 1; n <= p; ++n) {
         pref *= hx * rcp64(double(n + 1));
-        const double Inext = pref * col[(n + 1) * 64];
+        const double Inext = use_col ? pref * col[(n + 1) * 64] : iorder(t, pref, n + 1);
         Enext = cmul(Enext, e1);
         const double2 a = cmul(lb[n], Enext);
         const double2 c = cconj(cmul(lb[n], Eprev));
@@ -1315,7 +1323,8 @@ void Fmm::expansions(const double* sigma, hipStream_t s, bool m2l32) {
   gather_kernel<<<(unsigned)((N + 255) / 256), 256, 0, s>>>(N, perm.p, sigma, wnxs.p, wnys.p, qx.p,
                                                             qy.p);
   FmmLevel& leaf = lv[depth];
-  p2m_kernel<<<leaf.nbox, 64, (size_t)(p + 2) * 64 * sizeof(double), s>>>(p, kappa, leaf_start.p, leaf_cnt.p, leaf.cx.p, leaf.cy.p, xs.p,
+  const int col = p <= kColMaxOrder;
+  p2m_kernel<<<leaf.nbox, 64, col ? (size_t)(p + 2) * 64 * sizeof(double) : 0, s>>>(p, col, kappa, leaf_start.p, leaf_cnt.p, leaf.cx.p, leaf.cy.p, xs.p,
                                       ys.p, qx.p, qy.p, leaf.M.p);
   for (int l = depth - 1; l >= 2; --l) {
     if (use_mfma) {
@@ -1357,14 +1366,15 @@ void Fmm::apply(const double* sigma, double* partial, bool p2p_fp32, const doubl
   // the FP32-class (inner) operator also takes its M2L in FP32 when that is set up
   expansions(sigma, s, p2p_fp32 && want_m2l32 && use_mfma);
   FmmLevel& leaf = lv[depth];
-  const size_t sh_l =
-      (size_t)FB * (2 * sizeof(double2) + sizeof(float2)) + (size_t)(p + 1) * 64 * sizeof(double);
+  const int col = p <= kColMaxOrder;
+  const size_t sh_l = (size_t)FB * (2 * sizeof(double2) + sizeof(float2)) +
+                      (col ? (size_t)(p + 1) * 64 * sizeof(double) : 0);
   if (p2p_fp32)
-    l2p_p2p_kernel<true><<<leaf.nbox, FB, sh_l, s>>>(p, kappa, 1, leaf_start.p, leaf_cnt.p, nbp.p,
+    l2p_p2p_kernel<true><<<leaf.nbox, FB, sh_l, s>>>(p, kappa, 1, col, leaf_start.p, leaf_cnt.p, nbp.p,
                                                      nbi.p, leaf.cx.p, leaf.cy.p, leaf.L.p, xs.p, ys.p,
                                                      qx.p, qy.p, perm.p, tab, partial);
   else
-    l2p_p2p_kernel<false><<<leaf.nbox, FB, sh_l, s>>>(p, kappa, 1, leaf_start.p, leaf_cnt.p, nbp.p,
+    l2p_p2p_kernel<false><<<leaf.nbox, FB, sh_l, s>>>(p, kappa, 1, col, leaf_start.p, leaf_cnt.p, nbp.p,
                                                       nbi.p, leaf.cx.p, leaf.cy.p, leaf.L.p, xs.p,
                                                       ys.p, qx.p, qy.p, perm.p, tab, partial);
   YQ_HIP(hipGetLastError());
@@ -1373,8 +1383,10 @@ void Fmm::apply(const double* sigma, double* partial, bool p2p_fp32, const doubl
 void Fmm::apply_grad(const double* sigma, double* gpart, const double* tab, hipStream_t s) {
   expansions(sigma, s);
   FmmLevel& leaf = lv[depth];
-  const size_t sh = (size_t)FB * 2 * sizeof(double2) + (size_t)(p + 2) * 64 * sizeof(double);
-  l2p_p2p_grad_kernel<<<leaf.nbox, FB, sh, s>>>(p, kappa, leaf_start.p, leaf_cnt.p, nbp.p, nbi.p,
+  const int col = p <= kColMaxOrder;
+  const size_t sh =
+      (size_t)FB * 2 * sizeof(double2) + (col ? (size_t)(p + 2) * 64 * sizeof(double) : 0);
+  l2p_p2p_grad_kernel<<<leaf.nbox, FB, sh, s>>>(p, col, kappa, leaf_start.p, leaf_cnt.p, nbp.p, nbi.p,
                                                  leaf.cx.p, leaf.cy.p, leaf.L.p, xs.p, ys.p, qx.p,
                                                  qy.p, perm.p, N, tab, gpart);
   YQ_HIP(hipGetLastError());

@@ -23,7 +23,7 @@ struct yq_problem {
   bool batch_member = false;  // workspace for GMRES/forces comes from the batch
   std::unique_ptr<Fmm> fmm;     // far-field FMM (inner operator) when enabled
   std::unique_ptr<Fmm> fmm_hi;  // higher-order FP64 FMM for residuals (fmm_resid_order > 0)
-  int far_want = 8192;        // far-field plan parameter (far_plan)
+  int far_want = 16384;       // far-field plan parameter (far_plan)
 
   std::vector<double> h_pc;  // [n*5]
   DevBuf<double> pc, x, y, nx, ny, w, wnx, wny, panel_h, pcx, pcy, pr;
