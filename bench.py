@@ -179,8 +179,7 @@ def run_step(pb, parts, grid):
     pb.set_workload(parts)
     f = pb.boundary_label()
     pb.set_boundary_data(f)
-    sigma, info = pb.solve()
-    F, T, E = pb.forces(sigma)
+    sigma, info, F, T, E = pb.solve_forces()
     u = pb.eval_potential(sigma, grid)
     return info, u
 
@@ -446,7 +445,7 @@ def bench_large(args):
         pb.set_boundary_data(pb.boundary_label())
         pb.solve()
     pb.lib.yq_profile_enable(pb.h, 1)
-    for ph in range(6):
+    for ph in range(7):
         prof(pb, ph)
     lat, lat_setup = [], []
     for _ in range(max(args.steps, 1)):
@@ -517,7 +516,7 @@ def main():
         run_step(pb, parts, grid)
     torch.cuda.synchronize()
     pb.lib.yq_profile_enable(pb.h, 1)
-    for ph in range(6):
+    for ph in range(7):
         prof(pb, ph)
     lat = []
     far_passes = 0
@@ -540,6 +539,7 @@ def main():
     nfin, msfin = prof(pb, 2)
     ngr, msgr = prof(pb, 3)
     nqb, msqb = prof(pb, 4)
+    nfu, msfu = prof(pb, 6)
     pb.lib.yq_profile_enable(pb.h, 0)
     interactions = far_passes * float(N) * N + args.steps * grid.shape[0] * float(N)
     value = interactions / t_all
@@ -599,7 +599,9 @@ def main():
         "far32_ms": avg32 * 1e3,
         "far64_ms": avg64b * 1e3 if n64b else None,
         "finish_ms": msfin / max(nfin, 1),
-        "grad_far_ms": msgr / max(ngr, 1),
+        "grad_far_ms": msgr / ngr if ngr else None,
+        "resid_grad_fused_ms": msfu / nfu if nfu else None,
+        "grad_passes_unfused": ngr,
         "qbx_build_ms": msqb / max(nqb, 1),
         "fp64_path": {"latency_ms_p50": percentile(lat64, 0.5) * 1e3,
                       "solves_per_s": 1.0 / max(percentile(lat64, 0.5), 1e-12),

@@ -187,6 +187,17 @@ int yq_surface_gradient(yq_problem* prob, const double* sigma, double* gx, doubl
 int yq_forces(yq_problem* prob, const double* sigma, double gamma, double* force, double* torque,
               double* energy);
 
+/* Algorithm 1 end to end: yq_solve, then yq_forces of its sigma (steps a9 +
+ * a11), with the same arguments and results as those two calls.  With the
+ * direct far field, a YQ_MIXED solve computes the FP64 residual it expects to
+ * be its last one together with the gradient far field of the same sigma (one
+ * pass over the node pairs instead of two); the forces then reuse it.  If that
+ * residual was not the last, the gradient is computed afresh.  Results agree
+ * with yq_solve + yq_forces to rounding.  YQ_ENOCONV: not converged; sigma
+ * holds the last iterate and the forces are those of it.  Synchronous. */
+int yq_solve_forces(yq_problem* prob, const double* sigma0, double* sigma, yq_solve_info* info,
+                    double gamma, double* force, double* torque, double* energy);
+
 /* Off-surface potential u = D[sigma] (step a12, eq. intrep) at M targets:
  * dev tx, ty [M], dev u [M].  Panels whose nearest node is closer than
  * pot_beta*h use a pot_oversample-fold oversampled rule.  Asynchronous. */
@@ -317,7 +328,8 @@ int yq_server_cancel(yq_server* server, int64_t ticket);
 /* Per-phase GPU timers: with profiling enabled every launch of a phase is
  * bracketed by hipEvents on the problem's stream.  Phases: 0 FP64 far field,
  * 1 FP32 far field, 2 finish (chunk sum + near correction), 3 gradient far
- * field, 4 QBX build, 5 Krylov vector kernels.  yq_profile_read synchronises
+ * field, 4 QBX build, 5 Krylov vector kernels, 6 the fused FP64 far field +
+ * gradient of yq_solve_forces.  yq_profile_read synchronises
  * the stream and returns the number of timed launches and their summed
  * duration (ms) of one phase; reset != 0 clears that phase. */
 int yq_profile_enable(yq_problem* prob, int32_t enable);

@@ -157,6 +157,20 @@ class Problem:
                                        ctypes.byref(e)))
         return F.view(self.n, 2), T, e.value
 
+    def solve_forces(self, gamma=1.0, sigma0=None, out=None, allow_noconv=False):
+        """solve() then forces() of its sigma in one call (yq_solve_forces)."""
+        s0 = self._dev(sigma0) if sigma0 is not None else None
+        out = self._f64(self.N) if out is None else out
+        info = yq_solve_info()
+        F = self._f64(2 * self.n)
+        T = self._f64(self.n)
+        e = ctypes.c_double()
+        st = self.lib.yq_solve_forces(self.h, _ptr(s0), _ptr(out), ctypes.byref(info), float(gamma),
+                                      _ptr(F), _ptr(T), ctypes.byref(e))
+        if not (allow_noconv and st == _lib.YQ_ENOCONV):
+            self._check(st)
+        return out, {k: getattr(info, k) for k, _ in info._fields_}, F.view(self.n, 2), T, e.value
+
     def eval_potential(self, sigma, targets):
         sigma = self._dev(sigma)
         t = self._dev(targets).reshape(-1, 2)

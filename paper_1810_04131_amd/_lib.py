@@ -92,6 +92,8 @@ SIGNATURES = {
     "yq_solve": (c_int32, [P, P, P, ctypes.POINTER(yq_solve_info)]),
     "yq_surface_gradient": (c_int32, [P, P, P, P]),
     "yq_forces": (c_int32, [P, P, c_double, P, P, ctypes.POINTER(c_double)]),
+    "yq_solve_forces": (c_int32, [P, P, P, ctypes.POINTER(yq_solve_info), c_double, P, P,
+                                  ctypes.POINTER(c_double)]),
     "yq_eval_potential": (c_int32, [P, P, c_int64, P, P, P]),
     "yq_bessel": (c_int32, [c_int32, c_int32, c_int32, c_int64, P, P]),
     "yq_batch_create": (c_int32, [ctypes.POINTER(yq_params), ctypes.POINTER(c_void_p)]),

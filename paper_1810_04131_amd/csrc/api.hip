@@ -160,6 +160,20 @@ void apply_resid(yq_problem* pb, const double* sigma, double* out) {
                 pb->xpan.p, pb->xvals.p, sigma, out, pb->stream);
 }
 
+// The FP64 residual operator fused with the gradient far field of the same sigma
+// (direct far field only): out = A sigma, and pb->gpartial ready for the forces.
+void apply_resid_fused(yq_problem* pb, const double* sigma, double* out) {
+  {
+    Timed t(pb, 6);
+    pb->gpartial.reserve((size_t)pb->fp.chunks * 2 * pb->N);
+    launch_far_fused64(pb->view(), sigma, pb->fp, pb->partial.p, pb->gpartial.p, pb->stream);
+  }
+  Timed t(pb, 2);
+  launch_finish(pb->view(), pb->prm.qbx_window, pb->fp, pb->partial.p, nullptr, pb->W.p,
+                pb->xrow.p, pb->xpan.p, pb->xvals.p, sigma, out, pb->stream);
+  pb->grad_ready = true;
+}
+
 void apply_any(yq_problem* pb, const double* sigma, double* out, int prec) {
   if (prec == OP_RESID)
     apply_resid(pb, sigma, out);
@@ -695,7 +709,16 @@ int yq_apply_operator(yq_problem* pb, const double* sigma, double* out, int32_t 
   });
 }
 
-int yq_solve(yq_problem* pb, const double* sigma0, double* sigma, yq_solve_info* info) {
+}  // extern "C"
+
+namespace {
+
+// The solve of yq_solve.  fuse: the mixed-precision residual that is expected to
+// be the last one (the inner tolerance was set from tol / residual, so the
+// inner solve aims straight at the outer tolerance) also leaves the gradient far
+// field of sigma in pb->gpartial (pb->grad_ready), for yq_solve_forces.
+int solve_impl(yq_problem* pb, const double* sigma0, double* sigma, yq_solve_info* info,
+               bool fuse) {
   int status = YQ_OK;
   int rc = guarded(pb, [&] {
     require_ready(pb);
@@ -711,6 +734,9 @@ int yq_solve(yq_problem* pb, const double* sigma0, double* sigma, yq_solve_info*
     bool conv = false;
     bool r_current = false;  // r holds f - A sigma (FP64 operator) for the current sigma
     double* r = pb->kd.p;    // refinement residual
+    pb->grad_ready = false;
+    fuse = fuse && pb->prm.precision == YQ_MIXED && !pb->fmm && !pb->fmm_hi;
+    bool expect_last = false;  // the next residual is expected to meet the tolerance
     if (pb->prm.precision == YQ_FP64) {
       GmresResult R = gmres(pb, OP_RESID, pb->f.p, sigma, zero, pb->prm.tol, pb->prm.maxiter);
       inf.iterations = R.iterations;
@@ -730,7 +756,10 @@ int yq_solve(yq_problem* pb, const double* sigma0, double* sigma, yq_solve_info*
           YQ_HIP(hipMemcpyAsync(r, pb->f.p, N * sizeof(double), hipMemcpyDeviceToDevice, s));
           rel = 1.0;
         } else {
-          apply_resid(pb, sigma, pb->kw.p);
+          if (fuse && expect_last)
+            apply_resid_fused(pb, sigma, pb->kw.p);
+          else
+            apply_resid(pb, sigma, pb->kw.p);
           ++inf.matvecs_fp64;
           launch_axpby(-1.0, pb->kw.p, 1.0, pb->f.p, r, N, s);
           rel = fnorm > 0.0 ? std::sqrt(dot_host(pb, r, r)) / fnorm : 0.0;
@@ -749,11 +778,16 @@ int yq_solve(yq_problem* pb, const double* sigma0, double* sigma, yq_solve_info*
         budget -= R.iterations;
         launch_axpby(1.0, delta.p, 1.0, sigma, sigma, N, s);
         r_current = false;
+        pb->grad_ready = false;
+        expect_last = rel * std::min(itol, 0.5) <= pb->prm.tol;
       }
     }
     // final FP64 residual (the refinement loop's last one when sigma has not moved since)
     if (!r_current) {
-      apply_resid(pb, sigma, pb->kw.p);
+      if (fuse)
+        apply_resid_fused(pb, sigma, pb->kw.p);
+      else
+        apply_resid(pb, sigma, pb->kw.p);
       ++inf.matvecs_fp64;
       launch_axpby(-1.0, pb->kw.p, 1.0, pb->f.p, r, N, s);
     }
@@ -767,6 +801,14 @@ int yq_solve(yq_problem* pb, const double* sigma0, double* sigma, yq_solve_info*
   if (rc != YQ_OK) return rc;
   if (status != YQ_OK && pb) pb->err = "GMRES did not reach the tolerance";
   return status;
+}
+
+}  // namespace
+
+extern "C" {
+
+int yq_solve(yq_problem* pb, const double* sigma0, double* sigma, yq_solve_info* info) {
+  return solve_impl(pb, sigma0, sigma, info, false);
 }
 
 namespace {
@@ -801,29 +843,61 @@ int yq_surface_gradient(yq_problem* pb, const double* sigma, double* gx, double*
   });
 }
 
+}  // extern "C"
+
+namespace {
+
+// Forces, torques and energy of eqs. (force) and (torque) from sigma: the
+// surface gradient (its far field from pb->gpartial when the solve left it
+// there for this sigma, else computed now), then the per-particle sums.
+void forces_of(yq_problem* pb, const double* sigma, double gamma, double* force, double* torque,
+               double* energy) {
+  pb->gx.reserve(pb->N);
+  pb->gy.reserve(pb->N);
+  GeomView g = pb->view();
+  const FarPlan fp = pb->grad_ready ? pb->fp : far_grad(pb, sigma);
+  pb->grad_ready = false;
+  launch_finish_grad(g, pb->prm.qbx_window, fp, pb->gpartial.p, pb->WGx.p, pb->WGy.p, pb->xrow.p,
+                     pb->xpan.p, pb->xgvals.p, sigma, pb->gx.p, pb->gy.p, pb->stream);
+  launch_forces(g, pb->f.p, pb->gx.p, pb->gy.p, gamma, force, torque, pb->en.p, pb->stream);
+  std::vector<double> e(pb->n);
+  YQ_HIP(hipMemcpyAsync(e.data(), pb->en.p, pb->n * sizeof(double), hipMemcpyDeviceToHost,
+                        pb->stream));
+  YQ_HIP(hipStreamSynchronize(pb->stream));
+  if (energy) {
+    double t = 0.0;
+    for (double v : e) t += v;
+    *energy = t;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
 int yq_forces(yq_problem* pb, const double* sigma, double gamma, double* force, double* torque,
               double* energy) {
   return guarded(pb, [&] {
     require_ready(pb);
     YQ_REQUIRE(sigma && force && torque, YQ_EINVAL, "null argument");
     YQ_REQUIRE(pb->have_f, YQ_ESTATE, "boundary data not set");
-    pb->gx.reserve(pb->N);
-    pb->gy.reserve(pb->N);
-    GeomView g = pb->view();
-    const FarPlan fp = far_grad(pb, sigma);
-    launch_finish_grad(g, pb->prm.qbx_window, fp, pb->gpartial.p, pb->WGx.p, pb->WGy.p,
-                       pb->xrow.p, pb->xpan.p, pb->xgvals.p, sigma, pb->gx.p, pb->gy.p, pb->stream);
-    launch_forces(g, pb->f.p, pb->gx.p, pb->gy.p, gamma, force, torque, pb->en.p, pb->stream);
-    std::vector<double> e(pb->n);
-    YQ_HIP(hipMemcpyAsync(e.data(), pb->en.p, pb->n * sizeof(double), hipMemcpyDeviceToHost,
-                          pb->stream));
-    YQ_HIP(hipStreamSynchronize(pb->stream));
-    if (energy) {
-      double t = 0.0;
-      for (double v : e) t += v;
-      *energy = t;
-    }
+    pb->grad_ready = false;
+    forces_of(pb, sigma, gamma, force, torque, energy);
   });
+}
+
+int yq_solve_forces(yq_problem* pb, const double* sigma0, double* sigma, yq_solve_info* info,
+                    double gamma, double* force, double* torque, double* energy) {
+  if (pb && !(force && torque)) {
+    pb->err = "null argument";
+    return YQ_EINVAL;
+  }
+  const int st = solve_impl(pb, sigma0, sigma, info, true);
+  if (st != YQ_OK && st != YQ_ENOCONV) return st;
+  const int rc = guarded(pb, [&] { forces_of(pb, sigma, gamma, force, torque, energy); });
+  if (rc != YQ_OK) return rc;
+  if (st != YQ_OK) pb->err = "GMRES did not reach the tolerance";
+  return st;
 }
 
 int yq_eval_potential(yq_problem* pb, const double* sigma, int64_t M, const double* tx,

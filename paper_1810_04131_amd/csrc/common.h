@@ -215,6 +215,8 @@ void launch_finish(const GeomView& g, int win, const FarPlan& fp, const double* 
                    const double* xvals, const double* sigma, double* out, hipStream_t s);
 void launch_far_grad64(const GeomView& g, const double* sigma, const FarPlan& fp, double* partial,
                        hipStream_t s);
+void launch_far_fused64(const GeomView& g, const double* sigma, const FarPlan& fp,
+                        double* partial, double* gpartial, hipStream_t s);
 void launch_finish_grad(const GeomView& g, int win, const FarPlan& fp, const double* partial,
                         const double* WGx, const double* WGy, const int* xrow, const int* xpan,
                         const double* xgvals, const double* sigma, double* gx, double* gy,

@@ -167,6 +167,46 @@ __global__ __launch_bounds__(FAR_BS) void far_grad64_kernel(GeomView g,
   }
 }
 
+// Far field and its gradient in one pass: partial[chunk * N + i] as far64_kernel,
+// gpartial[(chunk * 2 + c) * N + i] as far_grad64_kernel.
+__global__ __launch_bounds__(FAR_BS) void far_fused64_kernel(GeomView g,
+                                                             const double* __restrict__ sigma,
+                                                             int chunk,
+                                                             double* __restrict__ partial,
+                                                             double* __restrict__ gpartial) {
+  __shared__ double2 sxy[FAR_BS];
+  __shared__ double2 sq[FAR_BS];
+  const int64_t N = g.N;
+  const int64_t i = blockIdx.x * (int64_t)FAR_BS + threadIdx.x;
+  const double xi = i < N ? g.x[i] : 0.0;
+  const double yi = i < N ? g.y[i] : 0.0;
+  const double kap2 = g.kappa * g.kappa;
+  const int64_t j0 = (int64_t)blockIdx.y * chunk;
+  const int64_t j1 = min(N, j0 + chunk);
+  const int64_t grp = blockIdx.x * (int64_t)(FAR_BS / FG) +
+                      __builtin_amdgcn_readfirstlane((int)(threadIdx.x / FG));
+  const bool live = grp * FG < N;
+  double acc = 0.0, ax = 0.0, ay = 0.0;
+  for (int64_t jb = j0; jb < j1; jb += FAR_BS) {
+    const int64_t j = jb + threadIdx.x;
+    __syncthreads();
+    if (j < j1) {
+      const double s = sigma[j];
+      sxy[threadIdx.x] = make_double2(g.x[j], g.y[j]);
+      sq[threadIdx.x] = make_double2(g.wnx[j] * s, g.wny[j] * s);
+    }
+    __syncthreads();
+    const int nb = (int)min((int64_t)FAR_BS, j1 - jb);
+    const int cls = live ? far64_class(g.fgrp, g.ftile, grp, jb / FT, g.kappa) : C64_GENERAL;
+    far_fused64_class_tile(cls, xi, yi, sxy, sq, nb, kap2, g.tab, acc, ax, ay);
+  }
+  if (i < N) {
+    partial[(int64_t)blockIdx.y * N + i] = acc;
+    gpartial[((int64_t)blockIdx.y * 2 + 0) * N + i] = ax;
+    gpartial[((int64_t)blockIdx.y * 2 + 1) * N + i] = ay;
+  }
+}
+
 // out_i = (kappa^2/2pi) sum_chunks partial + sum_window W sigma + sum_extra vals sigma
 __global__ void finish_kernel(GeomView g, int win, int chunks, const double* __restrict__ p64,
                               const float* __restrict__ p32, const double* __restrict__ W,
@@ -257,6 +297,13 @@ void launch_far32(const Far32View& v, const FarPlan& fp, float* partial, hipStre
   YQ_REQUIRE(fp.chunk % FT == 0, YQ_EINVAL, "far32: chunk is not a multiple of the tile");
   dim3 grid(fp.tblocks, fp.chunks);
   far32_kernel<<<grid, FAR_BS, 0, s>>>(v, fp.chunk, partial);
+  YQ_HIP(hipGetLastError());
+}
+
+void launch_far_fused64(const GeomView& g, const double* sigma, const FarPlan& fp,
+                        double* partial, double* gpartial, hipStream_t s) {
+  dim3 grid(fp.tblocks, fp.chunks);
+  far_fused64_kernel<<<grid, FAR_BS, 0, s>>>(g, sigma, fp.chunk, partial, gpartial);
   YQ_HIP(hipGetLastError());
 }
 

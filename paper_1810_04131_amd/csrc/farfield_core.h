@@ -281,6 +281,70 @@ __device__ __forceinline__ void far_grad64_class_tile(int cls, double xi, double
   }
 }
 
+// Double-layer value and gradient over a staged tile in one pass (the final
+// refinement residual and the surface gradient of the same density):
+// acc += K1(z)/z ((x-y).q) as far64_tile, (ax, ay) as far_grad64_tile.
+template <int NC, int H0, int H1>
+__device__ __forceinline__ void far_fused64_far_tile(double xi, double yi, const double2* sxy,
+                                                     const double2* sq, int nb, double kap2,
+                                                     const double* __restrict__ tab, double& acc,
+                                                     double& ax, double& ay) {
+  for (int k = 0; k < nb; ++k) {
+    const double2 p = sxy[k];
+    const double2 q = sq[k];
+    const double dx = xi - p.x, dy = yi - p.y;
+    const double r2 = fma(dx, dx, dy * dy);
+    double k0, k1z;
+    k0_k1z_64_large<NC, H0, H1>(kap2 * r2, k0, k1z, tab);
+    const double dq = fma(dx, q.x, dy * q.y);
+    acc += k1z * dq;
+    const double b = dq * (k0 + 2.0 * k1z) * rcp64(r2);
+    ax += k1z * q.x - b * dx;
+    ay += k1z * q.y - b * dy;
+  }
+}
+
+__device__ __forceinline__ void far_fused64_general_tile(double xi, double yi, const double2* sxy,
+                                                         const double2* sq, int nb, double kap2,
+                                                         const double* __restrict__ tab,
+                                                         double& acc, double& ax, double& ay) {
+  for (int k = 0; k < nb; ++k) {
+    const double2 p = sxy[k];
+    const double2 q = sq[k];
+    const double dx = xi - p.x, dy = yi - p.y;
+    const double r2 = fma(dx, dx, dy * dy);
+    if (r2 > 0.0) {
+      double k0, k1z;
+      k0_k1z_64(kap2 * r2, k0, k1z, tab);
+      const double dq = fma(dx, q.x, dy * q.y);
+      acc += k1z * dq;
+      const double b = dq * (k0 + 2.0 * k1z) * rcp64(r2);
+      ax += k1z * q.x - b * dx;
+      ay += k1z * q.y - b * dy;
+    }
+  }
+}
+
+__device__ __forceinline__ void far_fused64_class_tile(int cls, double xi, double yi,
+                                                       const double2* sxy, const double2* sq,
+                                                       int nb, double kap2,
+                                                       const double* __restrict__ tab,
+                                                       double& acc, double& ax, double& ay) {
+  switch (cls) {
+    case C64_Z8:
+      far_fused64_far_tile<12, T_H0_Z8, T_H1_Z8>(xi, yi, sxy, sq, nb, kap2, tab, acc, ax, ay);
+      break;
+    case C64_Z4:
+      far_fused64_far_tile<16, T_H0_Z4, T_H1_Z4>(xi, yi, sxy, sq, nb, kap2, tab, acc, ax, ay);
+      break;
+    case C64_Z2:
+      far_fused64_far_tile<21, T_H0, T_H1>(xi, yi, sxy, sq, nb, kap2, tab, acc, ax, ay);
+      break;
+    default:
+      far_fused64_general_tile(xi, yi, sxy, sq, nb, kap2, tab, acc, ax, ay);
+  }
+}
+
 // Window + extra-near correction of target i (local index) for density sg.
 __device__ __forceinline__ double correction_row(int64_t i, int64_t N, int P, int win,
                                                  const double* __restrict__ W,

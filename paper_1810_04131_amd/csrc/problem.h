@@ -48,9 +48,10 @@ struct yq_problem {
   DevBuf<double> V, kw, kr, kd, kpart, kred;
   DevBuf<double> gx, gy, en;
   DevBuf<double> delta;   // refinement correction
+  bool grad_ready = false;  // gpartial holds the direct gradient far field of the solve's sigma
 
   // per-phase timers
-  static constexpr int NPHASE = 6;
+  static constexpr int NPHASE = 7;
   bool prof = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[NPHASE];
   std::vector<hipEvent_t> pool;

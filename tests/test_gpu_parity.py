@@ -45,6 +45,14 @@ def _np(t):
     return t.detach().cpu().numpy()
 
 
+def _phase(pb, phase):
+    """(launches, total ms) of a profiled phase since the last read."""
+    import ctypes
+    n, ms = ctypes.c_int64(), ctypes.c_double()
+    pb._check(pb.lib.yq_profile_read(pb.h, phase, ctypes.byref(n), ctypes.byref(ms), 1))
+    return n.value, ms.value
+
+
 def _rel(a, b):
     return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
 
@@ -188,6 +196,39 @@ def test_gradient_forces_parity(small):
     assert abs(E - Er) < 1e-11 * abs(Er)
 
 
+def test_solve_forces_matches_solve_then_forces(small):
+    """The fused final residual + gradient pass gives the separate calls' results."""
+    kw = dict(tol=1e-9, precision=yq.YQ_MIXED)
+    pa = _problem(small["parts"], small["P"], small["p"], **kw)
+    pa.set_boundary_data(small["f"])
+    sa, ia = pa.solve()
+    Fa, Ta, Ea = pa.forces(sa, gamma=1.3)
+    pf = _problem(small["parts"], small["P"], small["p"], **kw)
+    pf.set_boundary_data(small["f"])
+    pf.lib.yq_profile_enable(pf.h, 1)
+    sf, inf_, Ff, Tf, Ef = pf.solve_forces(gamma=1.3)
+    nfu, _ = _phase(pf, 6)
+    assert nfu >= 1                       # the fused pass ran
+    assert inf_["iterations"] == ia["iterations"]
+    assert inf_["residual"] <= 1e-9
+    assert _rel(_np(sf), _np(sa)) < 1e-13
+    sc = max(np.abs(_np(Fa)).max(), np.abs(_np(Ta)).max(), abs(Ea))
+    assert np.abs(_np(Ff) - _np(Fa)).max() < 1e-12 * sc
+    assert np.abs(_np(Tf) - _np(Ta)).max() < 1e-12 * sc
+    assert abs(Ef - Ea) < 1e-12 * abs(Ea)
+    # against the oracle's forces of the oracle's sigma
+    g = np.stack([small["Gx"] @ small["sigma"], small["Gy"] @ small["sigma"]], 1)
+    Fr, Tr, _, Er = oracle.forces_torques(small["d"], small["f"], g, gamma=1.3)
+    scr = max(np.abs(Fr).max(), np.abs(Tr).max(), abs(Er))
+    assert np.abs(_np(Ff) - Fr).max() < 1e-7 * scr
+    # FP64 solves take the unfused path and still agree
+    p64 = _problem(small["parts"], small["P"], small["p"], tol=1e-12)
+    p64.set_boundary_data(small["f"])
+    s64, i64, F64, T64, E64 = p64.solve_forces(gamma=1.3)
+    assert i64["residual"] <= 1e-12
+    assert np.abs(_np(F64) - Fr).max() < 1e-9 * scr
+
+
 def test_potential_parity(small):
     pb = _problem(small["parts"], small["P"], small["p"])
     d = small["d"]
@@ -247,6 +288,13 @@ def test_medium_solve_residual_property(medium):
     F = _np(F)
     assert np.abs(F.sum(0)).max() < 1e-2 * np.abs(F).max()   # tanh arc edges: see oracle pins
     assert E > 0
+    # the fused final residual + gradient at full size gives the same forces
+    pm.lib.yq_profile_enable(pm.h, 1)
+    sf, inf_, Ff, Tf, Ef = pm.solve_forces()
+    assert _phase(pm, 6)[0] >= 1
+    assert inf_["residual"] <= 1e-8
+    assert _rel(_np(sf), sig) < 1e-12
+    assert _rel(_np(Ff), F) < 1e-11 and abs(Ef - E) < 1e-11 * abs(E)
 
 
 # ---- edge cases and error paths -----------------------------------------------------------------
