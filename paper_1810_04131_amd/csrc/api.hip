@@ -183,14 +183,15 @@ void apply_any(yq_problem* pb, const double* sigma, double* out, int prec) {
 
 // ---- GMRES -----------------------------------------------------------------------------------
 
+// Per-block partial dot products, summed on the host in block order.
 double dot_host(yq_problem* pb, const double* a, const double* b) {
   const int nb = krylov_blocks(pb->N);
   launch_multidot(a, 0, 1, b, pb->N, pb->kpart.p, nb, pb->stream);
-  launch_reduce(pb->kpart.p, 1, nb, pb->kred.p, pb->stream);
-  double v;
-  YQ_HIP(hipMemcpyAsync(&v, pb->kred.p, sizeof(double), hipMemcpyDeviceToHost, pb->stream));
+  pb->hpart.fit(nb * sizeof(double));
+  double* hp = (double*)pb->hpart.p;
+  YQ_HIP(hipMemcpyAsync(hp, pb->kpart.p, nb * sizeof(double), hipMemcpyDeviceToHost, pb->stream));
   YQ_HIP(hipStreamSynchronize(pb->stream));
-  return v;
+  return sum_partials(hp, nb);
 }
 
 struct GmresResult {
@@ -222,7 +223,9 @@ GmresResult gmres(yq_problem* pb, int prec, const double* b, double* x, bool x_z
   }
   if (x_zero) YQ_HIP(hipMemsetAsync(x, 0, N * sizeof(double), s));
 
-  std::vector<double> H((m + 1) * m), cs(m), sn(m), gv(m + 1), hbuf(2 * (m + 1) + 1);
+  std::vector<double> H((m + 1) * m), cs(m), sn(m), gv(m + 1);
+  pb->hpart.fit((size_t)(2 * (m + 1) + 1) * nb * sizeof(double));
+  const double* hp = (const double*)pb->hpart.p;
   bool first = true;
   while (true) {
     // r = b - A x
@@ -252,22 +255,24 @@ GmresResult gmres(yq_problem* pb, int prec, const double* b, double* x, bool x_z
       double* vn = V + (int64_t)(j + 1) * N;
       apply_any(pb, vj, w, prec);
       ++R.matvecs;
-      // classical Gram-Schmidt, twice
-      launch_multidot(V, N, j + 1, w, N, pb->kpart.p, nb, s);
-      launch_reduce(pb->kpart.p, j + 1, nb, pb->kred.p, s);
-      launch_update(w, V, N, j + 1, pb->kred.p, -1.0, N, s);
-      launch_multidot(V, N, j + 1, w, N, pb->kpart.p, nb, s);
-      launch_reduce(pb->kpart.p, j + 1, nb, pb->kred.p + (j + 1), s);
-      launch_update(w, V, N, j + 1, pb->kred.p + (j + 1), -1.0, N, s);
-      launch_multidot(w, 0, 1, w, N, pb->kpart.p, nb, s);
-      launch_reduce(pb->kpart.p, 1, nb, pb->kred.p + 2 * (j + 1), s);
-      YQ_HIP(hipMemcpyAsync(hbuf.data(), pb->kred.p, (2 * (j + 1) + 1) * sizeof(double),
-                            hipMemcpyDeviceToHost, s));
+      // classical Gram-Schmidt, twice; the per-block partial products of both
+      // passes and of |w|^2 go to the host in one copy, and each update kernel
+      // sums its pass's partials itself in the host's order
+      const int64_t pc = (int64_t)(j + 1) * nb;
+      double* kp = pb->kpart.p;
+      launch_multidot(V, N, j + 1, w, N, kp, nb, s);
+      launch_update_partial(w, V, N, j + 1, kp, nb, -1.0, N, s);
+      launch_multidot(V, N, j + 1, w, N, kp + pc, nb, s);
+      launch_update_partial(w, V, N, j + 1, kp + pc, nb, -1.0, N, s);
+      launch_multidot(w, 0, 1, w, N, kp + 2 * pc, nb, s);
+      YQ_HIP(hipMemcpyAsync((void*)hp, kp, (2 * pc + nb) * sizeof(double), hipMemcpyDeviceToHost,
+                            s));
       YQ_HIP(hipStreamSynchronize(s));
       ++R.iterations;
       double* hc = &H[(size_t)j * (m + 1)];  // column j, rows 0..j+1
-      for (int i = 0; i <= j; ++i) hc[i] = hbuf[i] + hbuf[j + 1 + i];
-      const double hn = std::sqrt(std::max(hbuf[2 * (j + 1)], 0.0));
+      for (int i = 0; i <= j; ++i)
+        hc[i] = sum_partials(hp + (int64_t)i * nb, nb) + sum_partials(hp + pc + (int64_t)i * nb, nb);
+      const double hn = std::sqrt(std::max(sum_partials(hp + 2 * pc, nb), 0.0));
       hc[j + 1] = hn;
       if (hn > 0.0) launch_axpby(1.0 / hn, w, 0.0, nullptr, vn, N, s);
       for (int i = 0; i < j; ++i) {
@@ -316,7 +321,7 @@ void ensure_krylov(yq_problem* pb) {
   pb->kw.reserve(N);
   pb->kr.reserve(N);
   pb->kd.reserve(N);
-  pb->kpart.reserve((size_t)krylov_blocks(N) * (m + 1));
+  pb->kpart.reserve((size_t)krylov_blocks(N) * (2 * (m + 1) + 1));
   pb->kred.reserve(2 * (m + 1) + 8);
 }
 

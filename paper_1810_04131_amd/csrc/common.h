@@ -226,7 +226,11 @@ void launch_finish_grad(const GeomView& g, int win, const FarPlan& fp, const dou
 int krylov_blocks(int64_t n);
 void launch_multidot(const double* V, int64_t ld, int k, const double* w, int64_t n, double* partial,
                      int nb, hipStream_t s);
-void launch_reduce(const double* partial, int k, int nb, double* out, hipStream_t s);
+// w += alpha V h with h[k] the in-order sum of partial[k * nb .. k * nb + nb)
+void launch_update_partial(double* w, const double* V, int64_t ld, int k, const double* partial,
+                           int nb, double alpha, int64_t n, hipStream_t s);
+// p[0] + p[1] + ... + p[nb - 1] in that order, on the host (the update kernel's order)
+double sum_partials(const double* p, int nb);
 void launch_update(double* w, const double* V, int64_t ld, int k, const double* h, double alpha,
                    int64_t n, hipStream_t s);
 void launch_axpby(double a, const double* x, double b, const double* y, double* out, int64_t n,

@@ -16,18 +16,6 @@ int krylov_blocks(int64_t n) {
   return (int)nb;
 }
 
-__device__ __forceinline__ double block_sum(double v, double* sh) {
-  sh[threadIdx.x] = v;
-  __syncthreads();
-  for (int o = KB / 2; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
-    __syncthreads();
-  }
-  double r = sh[0];
-  __syncthreads();
-  return r;
-}
-
 // Sum over the block in a fixed order: a shuffle tree inside each wavefront, then
 // the four wavefront sums in order.  Valid in thread 0.
 __device__ __forceinline__ double block_sum_waves(double v, double* sh) {
@@ -55,15 +43,25 @@ __global__ __launch_bounds__(KB) void multidot_kernel(const double* __restrict__
   if (threadIdx.x == 0) partial[(int64_t)k * nb + blockIdx.x] = s;
 }
 
-// out[k] = sum_b partial[k * nb + b]
-__global__ __launch_bounds__(KB) void reduce_kernel(const double* __restrict__ partial, int nb,
-                                                    double* __restrict__ out) {
-  __shared__ double sh[KB];
-  const int k = blockIdx.x;
-  double acc = 0.0;
-  for (int b = threadIdx.x; b < nb; b += KB) acc += partial[(int64_t)k * nb + b];
-  double s = block_sum(acc, sh);
-  if (threadIdx.x == 0) out[k] = s;
+// w[i] += alpha * sum_{k < kc} V[k][i] h[k], h[k] = sum_{b < nb} partial[k * nb + b]
+// summed in order b = 0, 1, ... (the order the host uses for the same sums).
+__global__ __launch_bounds__(KB) void update_partial_kernel(double* __restrict__ w,
+                                                            const double* __restrict__ V,
+                                                            int64_t ld, int kc,
+                                                            const double* __restrict__ partial,
+                                                            int nb, double alpha, int64_t n) {
+  extern __shared__ double h[];
+  for (int k = threadIdx.x; k < kc; k += KB) {
+    double t = 0.0;
+    for (int b = 0; b < nb; ++b) t += partial[(int64_t)k * nb + b];
+    h[k] = t;
+  }
+  __syncthreads();
+  const int64_t i = blockIdx.x * (int64_t)KB + threadIdx.x;
+  if (i >= n) return;
+  double s = 0.0;
+  for (int k = 0; k < kc; ++k) s = fma(V[(int64_t)k * ld + i], h[k], s);
+  w[i] = fma(alpha, s, w[i]);
 }
 
 // w[i] += alpha * sum_{k < kc} V[k][i] h[k]
@@ -98,9 +96,18 @@ void launch_multidot(const double* V, int64_t ld, int k, const double* w, int64_
   YQ_HIP(hipGetLastError());
 }
 
-void launch_reduce(const double* partial, int k, int nb, double* out, hipStream_t s) {
-  reduce_kernel<<<k, KB, 0, s>>>(partial, nb, out);
+void launch_update_partial(double* w, const double* V, int64_t ld, int k, const double* partial,
+                           int nb, double alpha, int64_t n, hipStream_t s) {
+  if (k < 1) return;
+  update_partial_kernel<<<(unsigned)((n + KB - 1) / KB), KB, k * sizeof(double), s>>>(
+      w, V, ld, k, partial, nb, alpha, n);
   YQ_HIP(hipGetLastError());
+}
+
+double sum_partials(const double* p, int nb) {
+  double t = 0.0;
+  for (int b = 0; b < nb; ++b) t += p[b];
+  return t;
 }
 
 void launch_update(double* w, const double* V, int64_t ld, int k, const double* h, double alpha,

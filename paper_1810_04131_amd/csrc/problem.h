@@ -46,6 +46,7 @@ struct yq_problem {
   DevBuf<double> f;
   // Krylov workspace
   DevBuf<double> V, kw, kr, kd, kpart, kred;
+  PinnedBuf hpart;   // host copy of Krylov partial dot products
   DevBuf<double> gx, gy, en;
   DevBuf<double> delta;   // refinement correction
   bool grad_ready = false;  // gpartial holds the direct gradient far field of the solve's sigma
