@@ -325,14 +325,15 @@ int yq_server_release(yq_server* server, int64_t ticket);
  * running FMM-lane request when its solve returns, at a later yq_server_step). */
 int yq_server_cancel(yq_server* server, int64_t ticket);
 
-/* Per-phase GPU timers: with profiling enabled every launch of a phase is
- * bracketed by hipEvents on the problem's stream.  Phases: 0 FP64 far field,
- * 1 FP32 far field, 2 finish (chunk sum + near correction), 3 gradient far
- * field, 4 QBX build, 5 Krylov vector kernels, 6 the fused FP64 far field +
- * gradient of yq_solve_forces.  yq_profile_read synchronises
- * the stream and returns the number of timed launches and their summed
- * duration (ms) of one phase; reset != 0 clears that phase. */
-int yq_profile_enable(yq_problem* prob, int32_t enable);
+/* Per-phase GPU timers: every launch of a timed phase is bracketed by
+ * hipEvents on the problem's stream.  Phases: 0 FP64 far field, 1 FP32 far
+ * field, 2 finish (chunk sum + near correction), 3 gradient far field, 4 QBX
+ * build, 5 Krylov vector kernels, 6 the fused FP64 far field + gradient of
+ * yq_solve_forces.  phase_mask: bit p times phase p; 0 times nothing (the
+ * default); -1 times every phase.  yq_profile_read synchronises the stream and
+ * returns the number of timed launches and their summed duration (ms) of one
+ * phase; reset != 0 clears that phase. */
+int yq_profile_enable(yq_problem* prob, int32_t phase_mask);
 int yq_profile_read(yq_problem* prob, int32_t phase, int64_t* launches, double* total_ms,
                     int32_t reset);
 

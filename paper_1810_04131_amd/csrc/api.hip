@@ -22,7 +22,7 @@ struct Timed {
   int phase;
   hipEvent_t a = nullptr;
   Timed(yq_problem* p, int ph) : pb(p), phase(ph) {
-    if (pb->prof) {
+    if (pb->prof_mask & (1u << ph)) {
       a = pb->event();
       YQ_HIP(hipEventRecord(a, pb->stream));
     }
@@ -126,7 +126,7 @@ void apply_op(yq_problem* pb, const double* sigma, double* out, int prec) {
     pb->pack32(sigma);
     {
       Timed t(pb, 1);
-      launch_far32(pb->far32(), pb->fp, pb->partial32.p, pb->stream);
+      launch_far32(pb->far32(), pb->fp, pb->partial32.p, pb->stream, pb->stop_dev);
     }
     Timed t(pb, 2);
     launch_finish(g, win, pb->fp, nullptr, pb->partial32.p, pb->W.p, pb->xrow.p, pb->xpan.p,
@@ -134,7 +134,7 @@ void apply_op(yq_problem* pb, const double* sigma, double* out, int prec) {
   } else {
     {
       Timed t(pb, 0);
-      launch_far64(g, sigma, pb->fp, pb->partial.p, pb->stream);
+      launch_far64(g, sigma, pb->fp, pb->partial.p, pb->stream, pb->stop_dev);
     }
     Timed t(pb, 2);
     launch_finish(g, win, pb->fp, pb->partial.p, nullptr, pb->W.p, pb->xrow.p, pb->xpan.p,
@@ -202,6 +202,145 @@ struct GmresResult {
   double rel = 0.0;  // residual estimate relative to ||b||
 };
 
+// Whether the operator of precision prec is the direct far field, whose kernels
+// honour the GMRES stop flag (the FMM's do not).
+bool direct_operator(const yq_problem* pb, int prec) {
+  if (prec == YQ_MIXED) return !pb->fmm;
+  if (prec == OP_RESID) return !pb->fmm_hi;
+  return true;
+}
+
+// Arnoldi of one GMRES cycle, bookkeeping on the host: after each step the
+// stream is synchronised and the Hessenberg column, its Givens rotation and the
+// residual estimate are done here.  Returns the number of steps k; H (host,
+// leading dimension m + 1) and gv hold the rotated columns and right-hand side.
+int arnoldi_sync(yq_problem* pb, int prec, int maxsteps, double bnorm, double rtol,
+                 std::vector<double>& H, std::vector<double>& gv, bool& done, GmresResult& R) {
+  const int64_t N = pb->N;
+  const int m = pb->prm.restart;
+  const int nb = krylov_blocks(N);
+  hipStream_t s = pb->stream;
+  double* V = pb->V.p;
+  double* w = pb->kw.p;
+  std::vector<double> cs(m), sn(m);
+  const double* hp = (const double*)pb->hpart.p;
+  int j = 0;
+  for (; j < maxsteps; ++j) {
+    double* vj = V + (int64_t)j * N;
+    double* vn = V + (int64_t)(j + 1) * N;
+    apply_any(pb, vj, w, prec);
+    ++R.matvecs;
+    // classical Gram-Schmidt, twice; the per-block partial products of both
+    // passes and of |w|^2 go to the host in one copy, and each update kernel
+    // sums its pass's partials itself in the host's order
+    const int64_t pc = (int64_t)(j + 1) * nb;
+    double* kp = pb->kpart.p;
+    launch_multidot(V, N, j + 1, w, N, kp, nb, s);
+    launch_update_partial(w, V, N, j + 1, kp, nb, -1.0, N, s);
+    launch_multidot(V, N, j + 1, w, N, kp + pc, nb, s);
+    launch_update_partial(w, V, N, j + 1, kp + pc, nb, -1.0, N, s);
+    launch_multidot(w, 0, 1, w, N, kp + 2 * pc, nb, s);
+    YQ_HIP(hipMemcpyAsync((void*)hp, kp, (2 * pc + nb) * sizeof(double), hipMemcpyDeviceToHost,
+                          s));
+    YQ_HIP(hipStreamSynchronize(s));
+    ++R.iterations;
+    double* hc = &H[(size_t)j * (m + 1)];  // column j, rows 0..j+1
+    for (int i = 0; i <= j; ++i)
+      hc[i] = sum_partials(hp + (int64_t)i * nb, nb) + sum_partials(hp + pc + (int64_t)i * nb, nb);
+    const double hn = std::sqrt(std::max(sum_partials(hp + 2 * pc, nb), 0.0));
+    hc[j + 1] = hn;
+    if (hn > 0.0) launch_axpby(1.0 / hn, w, 0.0, nullptr, vn, N, s);
+    for (int i = 0; i < j; ++i) {
+      const double t = cs[i] * hc[i] + sn[i] * hc[i + 1];
+      hc[i + 1] = -sn[i] * hc[i] + cs[i] * hc[i + 1];
+      hc[i] = t;
+    }
+    const double den = std::hypot(hc[j], hc[j + 1]);
+    cs[j] = den > 0.0 ? hc[j] / den : 1.0;
+    sn[j] = den > 0.0 ? hc[j + 1] / den : 0.0;
+    hc[j] = den;
+    hc[j + 1] = 0.0;
+    gv[j + 1] = -sn[j] * gv[j];
+    gv[j] = cs[j] * gv[j];
+    R.rel = std::fabs(gv[j + 1]) / bnorm;
+    if (R.rel <= rtol || hn == 0.0) {
+      done = true;
+      return j + 1;
+    }
+  }
+  return j;
+}
+
+// Arnoldi of one GMRES cycle with the bookkeeping on the device (arnoldi
+// kernel): the host queues step j + 1 before it waits for step j's status, so
+// the GPU does not idle while the host reads it.  When step j stops the cycle,
+// the already queued step j + 1 finds the device stop flag set: its far-field
+// launch and its Arnoldi kernel do nothing, and its cheap vector kernels write
+// only into unused Krylov storage.  Same results as arnoldi_sync up to the
+// rounding of the Givens arithmetic.
+int arnoldi_pipelined(yq_problem* pb, int prec, int maxsteps, double beta, double bnorm,
+                      double rtol, std::vector<double>& H, std::vector<double>& gv, bool& done,
+                      GmresResult& R) {
+  const int64_t N = pb->N;
+  const int m = pb->prm.restart;
+  const int ldh = m + 1;
+  const int nb = krylov_blocks(N);
+  hipStream_t s = pb->stream;
+  double* V = pb->V.p;
+  double* w = pb->kw.p;
+  double* dH = pb->gm.p;                         // [(m + 1) * m]
+  double* dcs = dH + (size_t)ldh * m;            // [m]
+  double* dsn = dcs + m;                         // [m]
+  double* dg = dsn + m;                          // [m + 1]
+  double* dinv = dg + m + 1;                     // [1]
+  double* dst = dinv + 1;                        // [4 m] per-step status
+  int* stop = pb->gstop.p;
+  double* hst = (double*)pb->hstat.p;            // host copy of the status [4 m]
+  launch_gmres_init(dg, m, beta, stop, s);
+  pb->stop_dev = stop;
+  int queued = 0, stopped = -1;
+  for (int j = 0; j < maxsteps; ++j) {
+    double* vj = V + (int64_t)j * N;
+    double* vn = V + (int64_t)(j + 1) * N;
+    apply_any(pb, vj, w, prec);
+    const int64_t pc = (int64_t)(j + 1) * nb;
+    double* kp = pb->kpart.p;
+    launch_multidot(V, N, j + 1, w, N, kp, nb, s);
+    launch_update_partial(w, V, N, j + 1, kp, nb, -1.0, N, s);
+    launch_multidot(V, N, j + 1, w, N, kp + pc, nb, s);
+    launch_update_partial(w, V, N, j + 1, kp + pc, nb, -1.0, N, s);
+    launch_multidot(w, 0, 1, w, N, kp + 2 * pc, nb, s);
+    launch_arnoldi(kp, nb, j, ldh, dH, dcs, dsn, dg, dinv, stop, bnorm, rtol, dst + 4 * j, s);
+    launch_scale(w, dinv, vn, N, s);
+    YQ_HIP(hipMemcpyAsync(hst + 4 * j, dst + 4 * j, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+    YQ_HIP(hipEventRecord(pb->step_ev[j & 1], s));
+    ++queued;
+    if (j >= 1) {
+      YQ_HIP(hipEventSynchronize(pb->step_ev[(j - 1) & 1]));
+      if (hst[4 * (j - 1) + 2] != 0.0) {
+        stopped = j - 1;
+        break;
+      }
+    }
+  }
+  pb->stop_dev = nullptr;
+  YQ_HIP(hipStreamSynchronize(s));
+  if (stopped < 0 && queued > 0 && hst[4 * (queued - 1) + 2] != 0.0) stopped = queued - 1;
+  const int k = stopped >= 0 ? stopped + 1 : queued;
+  R.iterations += k;
+  R.matvecs += k;
+  if (k > 0) {
+    R.rel = hst[4 * (k - 1)];
+    std::vector<double> t((size_t)ldh * k + k);
+    YQ_HIP(hipMemcpy(t.data(), dH, (size_t)ldh * k * sizeof(double), hipMemcpyDeviceToHost));
+    YQ_HIP(hipMemcpy(t.data() + (size_t)ldh * k, dg, k * sizeof(double), hipMemcpyDeviceToHost));
+    std::copy(t.begin(), t.begin() + (size_t)ldh * k, H.begin());
+    std::copy(t.begin() + (size_t)ldh * k, t.end(), gv.begin());
+  }
+  done = stopped >= 0;
+  return k;
+}
+
 // Solves A x = b with restarted GMRES; x holds the initial guess (x_zero: 0).
 // The operator is applied with precision prec; Arnoldi is FP64 (CGS2).
 GmresResult gmres(yq_problem* pb, int prec, const double* b, double* x, bool x_zero, double rtol,
@@ -209,7 +348,6 @@ GmresResult gmres(yq_problem* pb, int prec, const double* b, double* x, bool x_z
   GmresResult R;
   const int64_t N = pb->N;
   const int m = pb->prm.restart;
-  const int nb = krylov_blocks(N);
   hipStream_t s = pb->stream;
   double* V = pb->V.p;
   double* w = pb->kw.p;
@@ -223,9 +361,8 @@ GmresResult gmres(yq_problem* pb, int prec, const double* b, double* x, bool x_z
   }
   if (x_zero) YQ_HIP(hipMemsetAsync(x, 0, N * sizeof(double), s));
 
-  std::vector<double> H((m + 1) * m), cs(m), sn(m), gv(m + 1);
-  pb->hpart.fit((size_t)(2 * (m + 1) + 1) * nb * sizeof(double));
-  const double* hp = (const double*)pb->hpart.p;
+  const bool pipe = direct_operator(pb, prec);
+  std::vector<double> H((m + 1) * m), gv(m + 1);
   bool first = true;
   while (true) {
     // r = b - A x
@@ -248,54 +385,11 @@ GmresResult gmres(yq_problem* pb, int prec, const double* b, double* x, bool x_z
     launch_axpby(1.0 / beta, r, 0.0, nullptr, V, N, s);
     std::fill(gv.begin(), gv.end(), 0.0);
     gv[0] = beta;
-    int j = 0;
+    const int steps = std::min(m, maxit - R.iterations);
     bool done = false;
-    for (; j < m && R.iterations < maxit; ++j) {
-      double* vj = V + (int64_t)j * N;
-      double* vn = V + (int64_t)(j + 1) * N;
-      apply_any(pb, vj, w, prec);
-      ++R.matvecs;
-      // classical Gram-Schmidt, twice; the per-block partial products of both
-      // passes and of |w|^2 go to the host in one copy, and each update kernel
-      // sums its pass's partials itself in the host's order
-      const int64_t pc = (int64_t)(j + 1) * nb;
-      double* kp = pb->kpart.p;
-      launch_multidot(V, N, j + 1, w, N, kp, nb, s);
-      launch_update_partial(w, V, N, j + 1, kp, nb, -1.0, N, s);
-      launch_multidot(V, N, j + 1, w, N, kp + pc, nb, s);
-      launch_update_partial(w, V, N, j + 1, kp + pc, nb, -1.0, N, s);
-      launch_multidot(w, 0, 1, w, N, kp + 2 * pc, nb, s);
-      YQ_HIP(hipMemcpyAsync((void*)hp, kp, (2 * pc + nb) * sizeof(double), hipMemcpyDeviceToHost,
-                            s));
-      YQ_HIP(hipStreamSynchronize(s));
-      ++R.iterations;
-      double* hc = &H[(size_t)j * (m + 1)];  // column j, rows 0..j+1
-      for (int i = 0; i <= j; ++i)
-        hc[i] = sum_partials(hp + (int64_t)i * nb, nb) + sum_partials(hp + pc + (int64_t)i * nb, nb);
-      const double hn = std::sqrt(std::max(sum_partials(hp + 2 * pc, nb), 0.0));
-      hc[j + 1] = hn;
-      if (hn > 0.0) launch_axpby(1.0 / hn, w, 0.0, nullptr, vn, N, s);
-      for (int i = 0; i < j; ++i) {
-        const double t = cs[i] * hc[i] + sn[i] * hc[i + 1];
-        hc[i + 1] = -sn[i] * hc[i] + cs[i] * hc[i + 1];
-        hc[i] = t;
-      }
-      const double den = std::hypot(hc[j], hc[j + 1]);
-      cs[j] = den > 0.0 ? hc[j] / den : 1.0;
-      sn[j] = den > 0.0 ? hc[j + 1] / den : 0.0;
-      hc[j] = den;
-      hc[j + 1] = 0.0;
-      gv[j + 1] = -sn[j] * gv[j];
-      gv[j] = cs[j] * gv[j];
-      R.rel = std::fabs(gv[j + 1]) / bnorm;
-      if (R.rel <= rtol || hn == 0.0) {
-        ++j;
-        done = true;
-        break;
-      }
-    }
+    const int k = pipe ? arnoldi_pipelined(pb, prec, steps, beta, bnorm, rtol, H, gv, done, R)
+                       : arnoldi_sync(pb, prec, steps, bnorm, rtol, H, gv, done, R);
     // y = H^-1 g (upper triangular), x += V y
-    const int k = j;
     std::vector<double> yv(k);
     for (int i = k - 1; i >= 0; --i) {
       double t = gv[i];
@@ -323,6 +417,12 @@ void ensure_krylov(yq_problem* pb) {
   pb->kd.reserve(N);
   pb->kpart.reserve((size_t)krylov_blocks(N) * (2 * (m + 1) + 1));
   pb->kred.reserve(2 * (m + 1) + 8);
+  pb->gm.reserve((size_t)(m + 1) * m + 2 * m + (m + 1) + 1 + 4 * m);
+  pb->gstop.reserve(1);
+  pb->hstat.fit((size_t)4 * m * sizeof(double));
+  pb->hpart.fit((size_t)(2 * (m + 1) + 1) * krylov_blocks(N) * sizeof(double));
+  for (auto& e : pb->step_ev)
+    if (!e) YQ_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
 }
 
 void require_ready(const yq_problem* pb) {
@@ -433,6 +533,7 @@ int yq_set_particles(yq_problem* pb, int32_t n, const double* center_xy, const d
       amax = std::max(amax, A);
     }
     pb->ready = false;
+    pb->pot_fine_ready = false;
     pb->have_f = false;
     pb->n = n;
     pb->N = N;
@@ -912,17 +1013,38 @@ int yq_eval_potential(yq_problem* pb, const double* sigma, int64_t M, const doub
     YQ_REQUIRE(M >= 0, YQ_EINVAL, "M < 0");
     if (M == 0) return;
     YQ_REQUIRE(sigma && tx && ty && u, YQ_EINVAL, "null argument");
-    PotPlan pp = pot_plan(M, (int64_t)pb->n * pb->prm.panels_per_particle);
+    const int64_t npan = (int64_t)pb->n * pb->prm.panels_per_particle;
+    PotPlan pp = pot_plan(M, npan);
     pb->pot_partial.reserve((size_t)pp.chunks * M);
-    launch_potential(pb->view(), pb->consts, pb->prm.pot_oversample, pb->Lpot.p, pb->prm.pot_beta,
-                     sigma, M, tx, ty, pp, pb->pot_partial.p, u, pb->stream);
+    const int nsub = pb->prm.pot_oversample;
+    const size_t nf = (size_t)npan * nsub * Q;
+    GeomView g = pb->view();
+    PotFine pf{nsub, nullptr, nullptr, nullptr, nullptr, nullptr};
+    pb->pfs.reserve(nf);
+    if (!pb->pot_fine_ready) {
+      pb->pfx.reserve(nf);
+      pb->pfy.reserve(nf);
+      pb->pfwx.reserve(nf);
+      pb->pfwy.reserve(nf);
+    }
+    pf.x = pb->pfx.p;
+    pf.y = pb->pfy.p;
+    pf.wx = pb->pfwx.p;
+    pf.wy = pb->pfwy.p;
+    pf.s = pb->pfs.p;
+    if (!pb->pot_fine_ready) {
+      launch_pot_fine(g, pb->consts, nsub, pf, pb->stream);
+      pb->pot_fine_ready = true;
+    }
+    launch_potential(g, pf, pb->Lpot.p, pb->prm.pot_beta, sigma, M, tx, ty, pp,
+                     pb->pot_partial.p, u, pb->stream);
   });
 }
 
-int yq_profile_enable(yq_problem* pb, int32_t enable) {
+int yq_profile_enable(yq_problem* pb, int32_t phase_mask) {
   return guarded(pb, [&] {
     YQ_REQUIRE(pb, YQ_EINVAL, "null problem");
-    pb->prof = enable != 0;
+    pb->prof_mask = (uint32_t)phase_mask;
   });
 }
 

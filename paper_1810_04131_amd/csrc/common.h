@@ -124,6 +124,14 @@ struct PinnedBuf {
   }
 };
 
+// Uniform loads through a constant-address-space pointer become scalar loads.
+template <class T>
+using kptr = const __attribute__((address_space(4))) T*;
+template <class T>
+__device__ __forceinline__ kptr<T> as_k(const T* p) {
+  return (kptr<T>)p;
+}
+
 // Geometry of one problem as the kernels see it (all device pointers).
 struct GeomView {
   int n;                 // particles
@@ -207,9 +215,11 @@ void launch_far32_geom(const double* x, const double* y, int64_t N, double kappa
                        double4* grp, float2* rel, hipStream_t s);
 void launch_pack32(const float2* rel, const double* wnx, const double* wny, const double* sigma,
                    int64_t N, double qc, float4* src, hipStream_t s);
+// stop: optional device flag; the launch does nothing when it is set
 void launch_far64(const GeomView& g, const double* sigma, const FarPlan& fp, double* partial,
-                  hipStream_t s);
-void launch_far32(const Far32View& v, const FarPlan& fp, float* partial, hipStream_t s);
+                  hipStream_t s, const int* stop = nullptr);
+void launch_far32(const Far32View& v, const FarPlan& fp, float* partial, hipStream_t s,
+                  const int* stop = nullptr);
 void launch_finish(const GeomView& g, int win, const FarPlan& fp, const double* partial64,
                    const float* partial32, const double* W, const int* xrow, const int* xpan,
                    const double* xvals, const double* sigma, double* out, hipStream_t s);
@@ -231,6 +241,18 @@ void launch_update_partial(double* w, const double* V, int64_t ld, int k, const 
                            int nb, double alpha, int64_t n, hipStream_t s);
 // p[0] + p[1] + ... + p[nb - 1] in that order, on the host (the update kernel's order)
 double sum_partials(const double* p, int nb);
+// One Arnoldi step's bookkeeping on the device (the host-side GMRES does the same
+// on the host): Hessenberg column j (leading dimension ldh) from the partials of
+// the two Gram-Schmidt passes and of |w|^2 at part, the earlier Givens rotations
+// (cs, sn) applied to it, the new rotation, g updated, inv_hn = 1 / h_{j+1,j}
+// (0 at a breakdown), *stop set when |g_{j+1}| / bnorm <= rtol or at a breakdown,
+// and status = (|g_{j+1}| / bnorm, h_{j+1,j}, stop).  Nothing happens when *stop
+// is already set.
+void launch_arnoldi(const double* part, int nb, int j, int ldh, double* H, double* cs, double* sn,
+                    double* g, double* inv_hn, int* stop, double bnorm, double rtol,
+                    double* status, hipStream_t s);
+// g[0] = beta, g[1..m] = 0, *stop = 0 (start of a GMRES cycle)
+void launch_gmres_init(double* g, int m, double beta, int* stop, hipStream_t s);
 void launch_update(double* w, const double* V, int64_t ld, int k, const double* h, double alpha,
                    int64_t n, hipStream_t s);
 void launch_axpby(double a, const double* x, double b, const double* y, double* out, int64_t n,
@@ -247,7 +269,15 @@ struct PotPlan {
   int per;       // panels per chunk
 };
 PotPlan pot_plan(int64_t M, int64_t npan);
-void launch_potential(const GeomView& g, const Consts& c, int nsub, const double* L, double beta,
+// Oversampled panel rule of the off-surface potential: points, (weight) * (unit
+// normal) and the interpolated density, [panel * nsub * Q + k] each.
+struct PotFine {
+  int nsub;
+  double *x, *y, *wx, *wy, *s;
+};
+void launch_pot_fine(const GeomView& g, const Consts& c, int nsub, const PotFine& pf,
+                     hipStream_t s);
+void launch_potential(const GeomView& g, const PotFine& pf, const double* L, double beta,
                       const double* sigma, int64_t M, const double* tx, const double* ty,
                       const PotPlan& pp, double* partial, double* u, hipStream_t s);
 

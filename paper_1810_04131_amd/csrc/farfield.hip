@@ -36,10 +36,14 @@ FarPlan far_plan(int64_t nt, int64_t ns, int block, int want) {
   return fp;
 }
 
+// stop (may be null): when *stop is set the launch does nothing (an operator
+// application that a converged GMRES no longer needs).
 __global__ __launch_bounds__(FAR_BS) void far64_kernel(GeomView g, const double* __restrict__ sigma,
-                                                       int chunk, double* __restrict__ partial) {
+                                                       int chunk, double* __restrict__ partial,
+                                                       const int* __restrict__ stop) {
   __shared__ double2 sxy[FAR_BS];
   __shared__ double2 sq[FAR_BS];
+  if (stop && *as_k(stop)) return;   // uniform over the grid
   const int64_t N = g.N;
   const int64_t i = blockIdx.x * (int64_t)FAR_BS + threadIdx.x;
   const double xi = i < N ? g.x[i] : 0.0;
@@ -72,7 +76,9 @@ __global__ __launch_bounds__(FAR_BS) void far64_kernel(GeomView g, const double*
 // block = 256 targets x one source chunk (grid.y).  No LDS and no barrier: the
 // sources reach every lane through scalar loads (far32_range).
 __global__ __launch_bounds__(FAR_BS) void far32_kernel(Far32View v, int chunk,
-                                                       float* __restrict__ partial) {
+                                                       float* __restrict__ partial,
+                                                       const int* __restrict__ stop) {
+  if (stop && *as_k(stop)) return;   // as in far64_kernel
   const int64_t i = blockIdx.x * (int64_t)FAR_BS + threadIdx.x;
   const int64_t g = blockIdx.x * (int64_t)(FAR_BS / FG) +
                     __builtin_amdgcn_readfirstlane((int)(threadIdx.x / FG));
@@ -271,9 +277,9 @@ __global__ void finish_grad_kernel(GeomView g, int win, int chunks, const double
 }
 
 void launch_far64(const GeomView& g, const double* sigma, const FarPlan& fp, double* partial,
-                  hipStream_t s) {
+                  hipStream_t s, const int* stop) {
   dim3 grid(fp.tblocks, fp.chunks);
-  far64_kernel<<<grid, FAR_BS, 0, s>>>(g, sigma, fp.chunk, partial);
+  far64_kernel<<<grid, FAR_BS, 0, s>>>(g, sigma, fp.chunk, partial, stop);
   YQ_HIP(hipGetLastError());
 }
 
@@ -293,10 +299,11 @@ void launch_pack32(const float2* rel, const double* wnx, const double* wny, cons
   YQ_HIP(hipGetLastError());
 }
 
-void launch_far32(const Far32View& v, const FarPlan& fp, float* partial, hipStream_t s) {
+void launch_far32(const Far32View& v, const FarPlan& fp, float* partial, hipStream_t s,
+                  const int* stop) {
   YQ_REQUIRE(fp.chunk % FT == 0, YQ_EINVAL, "far32: chunk is not a multiple of the tile");
   dim3 grid(fp.tblocks, fp.chunks);
-  far32_kernel<<<grid, FAR_BS, 0, s>>>(v, fp.chunk, partial);
+  far32_kernel<<<grid, FAR_BS, 0, s>>>(v, fp.chunk, partial, stop);
   YQ_HIP(hipGetLastError());
 }
 

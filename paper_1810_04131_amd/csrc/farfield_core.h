@@ -88,14 +88,6 @@ __device__ __forceinline__ float far32_tile(double xi, double yi, const double2*
 // (rel x, rel y, q'x, q'y), q' = w nu sigma sqrt(log2 e) / kappa, and read
 // through scalar loads: every lane of a wavefront needs the same source.
 
-// Uniform loads through a constant-address-space pointer become scalar loads.
-template <class T>
-using kptr = const __attribute__((address_space(4))) T*;
-template <class T>
-__device__ __forceinline__ kptr<T> as_k(const T* p) {
-  return (kptr<T>)p;
-}
-
 
 // Far pairs: with D = s (x_i - y_j), Z2 = |D|^2 = (z log2 e)^2, Y = 1/sqrt(Z2),
 // K1(z)/z ((x_i - y_j) . q) = 2^-Z h1(2 log2(e) Y) (Y / sqrt(Z)) (D . q').  H is

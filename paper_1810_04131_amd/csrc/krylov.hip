@@ -89,6 +89,77 @@ __global__ void scale_kernel(const double* __restrict__ x, const double* __restr
   out[i] = x[i] * inv[0];
 }
 
+constexpr int MAXR = 200;   // largest restart length (checked with the parameters)
+
+__global__ __launch_bounds__(64) void arnoldi_kernel(const double* __restrict__ part, int nb, int j,
+                                                     int ldh, double* __restrict__ H,
+                                                     double* __restrict__ cs,
+                                                     double* __restrict__ sn,
+                                                     double* __restrict__ g,
+                                                     double* __restrict__ inv_hn,
+                                                     int* __restrict__ stop, double bnorm,
+                                                     double rtol, double* __restrict__ status) {
+  __shared__ double hc[MAXR + 2];
+  if (*stop) return;   // uniform: the cycle has already stopped
+  const int64_t pc = (int64_t)(j + 1) * nb;
+  for (int i = threadIdx.x; i <= j; i += 64) {
+    double a = 0.0, b = 0.0;
+    for (int q = 0; q < nb; ++q) a += part[(int64_t)i * nb + q];
+    for (int q = 0; q < nb; ++q) b += part[pc + (int64_t)i * nb + q];
+    hc[i] = a + b;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  double h2 = 0.0;
+  for (int q = 0; q < nb; ++q) h2 += part[2 * pc + q];
+  const double hn = sqrt(fmax(h2, 0.0));
+  hc[j + 1] = hn;
+  for (int i = 0; i < j; ++i) {
+    const double t = cs[i] * hc[i] + sn[i] * hc[i + 1];
+    hc[i + 1] = -sn[i] * hc[i] + cs[i] * hc[i + 1];
+    hc[i] = t;
+  }
+  const double den = hypot(hc[j], hc[j + 1]);
+  const double c = den > 0.0 ? hc[j] / den : 1.0;
+  const double sv = den > 0.0 ? hc[j + 1] / den : 0.0;
+  cs[j] = c;
+  sn[j] = sv;
+  hc[j] = den;
+  hc[j + 1] = 0.0;
+  const double gj = g[j];
+  g[j + 1] = -sv * gj;
+  g[j] = c * gj;
+  const double rel = fabs(sv * gj) / bnorm;
+  for (int i = 0; i <= j + 1; ++i) H[(int64_t)j * ldh + i] = hc[i];
+  inv_hn[0] = hn > 0.0 ? 1.0 / hn : 0.0;
+  const int st = (rel <= rtol || hn == 0.0) ? 1 : 0;
+  *stop = st;
+  status[0] = rel;
+  status[1] = hn;
+  status[2] = (double)st;
+}
+
+__global__ void gmres_init_kernel(double* __restrict__ g, int m, double beta,
+                                  int* __restrict__ stop) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i <= m) g[i] = i == 0 ? beta : 0.0;
+  if (i == 0) *stop = 0;
+}
+
+void launch_arnoldi(const double* part, int nb, int j, int ldh, double* H, double* cs, double* sn,
+                    double* g, double* inv_hn, int* stop, double bnorm, double rtol,
+                    double* status, hipStream_t s) {
+  YQ_REQUIRE(j >= 0 && j + 1 < ldh && j < MAXR, YQ_EINVAL, "arnoldi: column out of range");
+  arnoldi_kernel<<<1, 64, 0, s>>>(part, nb, j, ldh, H, cs, sn, g, inv_hn, stop, bnorm, rtol,
+                                  status);
+  YQ_HIP(hipGetLastError());
+}
+
+void launch_gmres_init(double* g, int m, double beta, int* stop, hipStream_t s) {
+  gmres_init_kernel<<<(unsigned)((m + 1 + 255) / 256), 256, 0, s>>>(g, m, beta, stop);
+  YQ_HIP(hipGetLastError());
+}
+
 void launch_multidot(const double* V, int64_t ld, int k, const double* w, int64_t n,
                      double* partial, int nb, hipStream_t s) {
   if (k < 1) return;

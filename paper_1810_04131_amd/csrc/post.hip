@@ -67,8 +67,8 @@ __global__ __launch_bounds__(FB) void forces_kernel(GeomView g, const double* __
 
 // u(z) = sum over panels of the 16-point rule, or of an nsub-fold oversampled
 // rule (sigma interpolated) for panels whose nearest node is closer than beta*h.
-// Grid: (target blocks of 64) x (panel chunks); chunk partials are summed in a
-// fixed order by potential_finish_kernel.
+// Grid: (target blocks of 64) x (panel chunks); the chunk partials,
+// [target * chunks + chunk], are summed in a fixed order by potential_finish_kernel.
 PotPlan pot_plan(int64_t M, int64_t npan) {
   PotPlan pp;
   pp.tblocks = (int)((M + 63) / 64);
@@ -80,13 +80,61 @@ PotPlan pot_plan(int64_t M, int64_t npan) {
   return pp;
 }
 
-__global__ __launch_bounds__(64) void potential_kernel(GeomView g, Consts c, int nsub,
-                                                       const double* __restrict__ L, double beta,
+// Oversampled source points of every panel for targets near it: point
+// k = sub * Q + gq of panel J lies at the exact parametrisation of sub-panel sub
+// (Gauss-Legendre node gq), with (fwx, fwy) = (weight) * (unit normal) of the
+// oversampled rule.  Per geometry; layout [J * nsub * Q + k].
+__global__ void pot_fine_kernel(GeomView g, Consts c, int nsub, double* __restrict__ fx,
+                                double* __restrict__ fy, double* __restrict__ fwx,
+                                double* __restrict__ fwy) {
+  const int F = nsub * Q;
+  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)g.n * g.P * F) return;
+  const int64_t J = idx / F;
+  const int k = (int)(idx - J * F);
+  const int sub = k / Q, gq = k - sub * Q;
+  const int pid = (int)(J / g.P), kj = (int)(J % g.P);
+  const double* pp = g.pc + 5 * pid;
+  double sa, ca;
+  sincos(pp[2], &sa, &ca);
+  const double xl = -1.0 + (2.0 * sub + c.xg[gq] + 1.0) / nsub;
+  const double t = 2.0 * PI / g.P * (kj + 0.5 * (xl + 1.0));
+  double st, ct;
+  sincos(t, &st, &ct);
+  const double ex = pp[3] * ct, ey = pp[4] * st;
+  const double ddx = -pp[3] * st, ddy = pp[4] * ct;
+  const double gx = ca * ddx - sa * ddy, gy = sa * ddx + ca * ddy;
+  // w / |gamma'| = (pi / P / nsub) wg, so (w nu) = (pi / P / nsub) wg (gy, -gx)
+  const double wq = (PI / g.P / nsub) * c.wg[gq];
+  fx[idx] = pp[0] + ca * ex - sa * ey;
+  fy[idx] = pp[1] + sa * ex + ca * ey;
+  fwx[idx] = wq * gy;
+  fwy[idx] = -wq * gx;
+}
+
+// sigma interpolated to the oversampled points: fs[J * F + k] = sum_m L[k][m] sigma[J * Q + m].
+__global__ void pot_fine_sigma_kernel(int64_t npan, int nsub, const double* __restrict__ L,
+                                      const double* __restrict__ sigma, double* __restrict__ fs) {
+  const int F = nsub * Q;
+  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (idx >= npan * F) return;
+  const int64_t J = idx / F;
+  const int k = (int)(idx - J * F);
+  const double* Lr = L + (int64_t)k * Q;
+  const double* sg = sigma + J * Q;
+  double t = 0.0;
+#pragma unroll
+  for (int m = 0; m < Q; ++m) t = fma(Lr[m], sg[m], t);
+  fs[idx] = t;
+}
+
+__global__ __launch_bounds__(64) void potential_kernel(GeomView g, PotFine pf, double beta,
                                                        const double* __restrict__ sigma,
                                                        int64_t M, const double* __restrict__ tx,
                                                        const double* __restrict__ ty, int per,
                                                        double* __restrict__ partial) {
-  const int64_t a0 = blockIdx.x * (int64_t)64 + threadIdx.x;
+  const int lane = threadIdx.x;
+  const int64_t a0 = blockIdx.x * (int64_t)64 + lane;
   const bool active = a0 < M;
   const int64_t a = active ? a0 : 0;
   const double zx = tx[a], zy = ty[a];
@@ -94,58 +142,58 @@ __global__ __launch_bounds__(64) void potential_kernel(GeomView g, Consts c, int
   const int64_t npan = (int64_t)g.n * g.P;
   const int64_t J0 = (int64_t)blockIdx.y * per;
   const int64_t J1 = min(npan, J0 + per);
+  const int F = pf.nsub * Q;
+  kptr<double> sx = as_k(g.x), sy = as_k(g.y), swx = as_k(g.wnx), swy = as_k(g.wny);
+  kptr<double> ssg = as_k(sigma);
   double acc = 0.0;
   for (int64_t J = J0; J < J1; ++J) {
     const int64_t b = J * Q;
     double d2 = 1e300, part = 0.0;
     for (int m = 0; m < Q; ++m) {
-      const double dx = zx - g.x[b + m], dy = zy - g.y[b + m];
+      const double dx = zx - sx[b + m], dy = zy - sy[b + m];
       const double r2 = dx * dx + dy * dy;
       d2 = fmin(d2, r2);
-      part += k1z_64(kap2 * r2, g.tab) * (dx * g.wnx[b + m] + dy * g.wny[b + m]) * sigma[b + m];
+      part += k1z_64(kap2 * r2, g.tab) * (dx * swx[b + m] + dy * swy[b + m]) * ssg[b + m];
     }
     const double bh = beta * g.panel_h[J];
-    if (d2 >= bh * bh) {
-      acc += part;
-      continue;
-    }
-    // oversampled: sub-panel nodes from the exact parametrisation
-    const int pid = (int)(J / g.P), kj = (int)(J % g.P);
-    const double* pp = g.pc + 5 * pid;
-    double sa, ca;
-    sincos(pp[2], &sa, &ca);
-    for (int sub = 0; sub < nsub; ++sub) {
-      for (int gq = 0; gq < Q; ++gq) {
-        const double xl = -1.0 + (2.0 * sub + c.xg[gq] + 1.0) / nsub;
-        const double t = 2.0 * PI / g.P * (kj + 0.5 * (xl + 1.0));
-        double st, ct;
-        sincos(t, &st, &ct);
-        const double ex = pp[3] * ct, ey = pp[4] * st;
-        const double ddx = -pp[3] * st, ddy = pp[4] * ct;
-        const double yx = pp[0] + ca * ex - sa * ey;
-        const double yy = pp[1] + sa * ex + ca * ey;
-        const double gx = ca * ddx - sa * ddy, gy = sa * ddx + ca * ddy;
-        const double sp = sqrt(gx * gx + gy * gy);
-        const double wf = (PI / g.P / nsub) * c.wg[gq] * sp;
-        const double* Lr = L + (sub * Q + gq) * Q;
-        double sf = 0.0;
-        for (int m = 0; m < Q; ++m) sf = fma(Lr[m], sigma[b + m], sf);
-        const double dx = zx - yx, dy = zy - yy;
-        const double r2 = dx * dx + dy * dy;
-        acc += k1z_64(kap2 * r2, g.tab) * (dx * gy - dy * gx) / sp * wf * sf;
+    const bool near = active && d2 < bh * bh;
+    if (!near) acc += part;
+    // oversampled rule for the lanes near this panel, one lane at a time: the
+    // whole wavefront evaluates its points for that lane's target and sums them
+    uint64_t nm = __ballot(near);
+    const double* fx = pf.x + J * F;
+    const double* fy = pf.y + J * F;
+    const double* fwx = pf.wx + J * F;
+    const double* fwy = pf.wy + J * F;
+    const double* fs = pf.s + J * F;
+    while (nm) {
+      const int t = __ffsll((unsigned long long)nm) - 1;
+      nm &= nm - 1;
+      const double ux = __shfl(zx, t, 64), uy = __shfl(zy, t, 64);
+      double sum = 0.0;
+      for (int k = lane; k < F; k += 64) {
+        const double dx = ux - fx[k], dy = uy - fy[k];
+        sum += k1z_64(kap2 * (dx * dx + dy * dy), g.tab) * (dx * fwx[k] + dy * fwy[k]) * fs[k];
       }
+      for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 64);
+      if (lane == t) acc += sum;
     }
   }
-  if (active) partial[(int64_t)blockIdx.y * M + a] = acc;
+  if (active) partial[a * gridDim.y + blockIdx.y] = acc;
 }
 
-__global__ void potential_finish_kernel(const double* __restrict__ partial, int chunks, int64_t M,
-                                        double scale, double* __restrict__ u) {
-  const int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (a >= M) return;
+// u[a] = scale * sum_c partial[a * chunks + c]: one wavefront per target, each
+// lane summing every 64th chunk in order, then a fixed butterfly.
+__global__ __launch_bounds__(256) void potential_finish_kernel(const double* __restrict__ partial,
+                                                               int chunks, int64_t M, double scale,
+                                                               double* __restrict__ u) {
+  const int64_t a = blockIdx.x * (int64_t)4 + threadIdx.x / 64;
+  const int lane = threadIdx.x & 63;
+  if (a >= M) return;   // uniform over the wavefront
   double s = 0.0;
-  for (int c = 0; c < chunks; ++c) s += partial[(int64_t)c * M + a];
-  u[a] = s * scale;
+  for (int c = lane; c < chunks; c += 64) s += partial[a * chunks + c];
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  if (lane == 0) u[a] = s * scale;
 }
 
 __global__ void bessel_kernel(int kind, int order, int prec, int64_t n, const double* __restrict__ z,
@@ -195,14 +243,27 @@ void launch_forces(const GeomView& g, const double* f, const double* gx, const d
   YQ_HIP(hipGetLastError());
 }
 
-void launch_potential(const GeomView& g, const Consts& c, int nsub, const double* L, double beta,
+void launch_pot_fine(const GeomView& g, const Consts& c, int nsub, const PotFine& pf,
+                     hipStream_t s) {
+  const int64_t n = (int64_t)g.n * g.P * nsub * Q;
+  if (n == 0) return;
+  pot_fine_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(g, c, nsub, pf.x, pf.y, pf.wx, pf.wy);
+  YQ_HIP(hipGetLastError());
+}
+
+void launch_potential(const GeomView& g, const PotFine& pf, const double* L, double beta,
                       const double* sigma, int64_t M, const double* tx, const double* ty,
                       const PotPlan& pp, double* partial, double* u, hipStream_t s) {
   if (M == 0) return;
-  dim3 grid(pp.tblocks, pp.chunks);
-  potential_kernel<<<grid, 64, 0, s>>>(g, c, nsub, L, beta, sigma, M, tx, ty, pp.per, partial);
+  const int64_t npan = (int64_t)g.n * g.P;
+  const int64_t nf = npan * pf.nsub * Q;
+  pot_fine_sigma_kernel<<<(unsigned)((nf + 255) / 256), 256, 0, s>>>(npan, pf.nsub, L, sigma,
+                                                                      pf.s);
   YQ_HIP(hipGetLastError());
-  potential_finish_kernel<<<(unsigned)((M + 255) / 256), 256, 0, s>>>(
+  dim3 grid(pp.tblocks, pp.chunks);
+  potential_kernel<<<grid, 64, 0, s>>>(g, pf, beta, sigma, M, tx, ty, pp.per, partial);
+  YQ_HIP(hipGetLastError());
+  potential_finish_kernel<<<(unsigned)((M + 3) / 4), 256, 0, s>>>(
       partial, pp.chunks, M, g.kappa * g.kappa / (2.0 * PI), u);
   YQ_HIP(hipGetLastError());
 }

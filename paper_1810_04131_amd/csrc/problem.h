@@ -33,6 +33,8 @@ struct yq_problem {
   DevBuf<float2> frel;
   DevBuf<float4> fsrc;
   DevBuf<double> pot_partial;
+  DevBuf<double> pfx, pfy, pfwx, pfwy, pfs;   // oversampled potential rule (PotFine)
+  bool pot_fine_ready = false;                // pf* hold this geometry's points
   DevBuf<int> nb_ptr, nb_idx, bad, ncnt;
   DevBuf<int> xrow, xpan;
   int64_t x_total = 0;
@@ -47,13 +49,19 @@ struct yq_problem {
   // Krylov workspace
   DevBuf<double> V, kw, kr, kd, kpart, kred;
   PinnedBuf hpart;   // host copy of Krylov partial dot products
+  // device-side Arnoldi bookkeeping (H, rotations, g, 1 / h_{j+1,j}, step status)
+  DevBuf<double> gm;
+  DevBuf<int> gstop;            // set when the GMRES cycle has stopped
+  PinnedBuf hstat;              // host copy of the step status
+  hipEvent_t step_ev[2] = {nullptr, nullptr};
+  const int* stop_dev = nullptr;   // passed to the far-field launches while set
   DevBuf<double> gx, gy, en;
   DevBuf<double> delta;   // refinement correction
   bool grad_ready = false;  // gpartial holds the direct gradient far field of the solve's sigma
 
   // per-phase timers
   static constexpr int NPHASE = 7;
-  bool prof = false;
+  uint32_t prof_mask = 0;   // bit p: time the launches of phase p
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[NPHASE];
   std::vector<hipEvent_t> pool;
 
@@ -74,6 +82,8 @@ struct yq_problem {
         (void)hipEventDestroy(p.second);
       }
     for (auto e : pool) (void)hipEventDestroy(e);
+    for (auto e : step_ev)
+      if (e) (void)hipEventDestroy(e);
   }
 
   Far32View far32() const {

@@ -196,6 +196,35 @@ def test_gradient_forces_parity(small):
     assert abs(E - Er) < 1e-11 * abs(Er)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_restarted_gmres_and_iteration_limit(small, precision):
+    """Short restart cycles (several cycles, a stop inside a cycle) and an iteration
+    limit that ends a cycle early: the device-side Arnoldi steps count exactly."""
+    prec = yq.YQ_FP64 if precision == "fp64" else yq.YQ_MIXED
+    tol = 1e-11 if precision == "fp64" else 1e-9
+    pb = _problem(small["parts"], small["P"], small["p"], tol=tol, precision=prec, restart=4,
+                  maxiter=400)
+    pb.set_boundary_data(small["f"])
+    sig, info = pb.solve()
+    assert info["residual"] <= tol
+    assert info["outer_steps"] >= 1
+    assert _rel(_np(sig), small["sigma"]) < 50 * tol
+    # the same problem with one long cycle takes no more iterations than restarted
+    pl = _problem(small["parts"], small["P"], small["p"], tol=tol, precision=prec, restart=100)
+    pl.set_boundary_data(small["f"])
+    sl, il = pl.solve()
+    if precision == "fp64":   # full GMRES minimises over the larger space
+        assert il["iterations"] <= info["iterations"]
+    assert _rel(_np(sl), small["sigma"]) < 50 * tol
+    # an iteration limit of 6 with cycles of 4: exactly 6 Arnoldi steps, not converged
+    pm = _problem(small["parts"], small["P"], small["p"], tol=1e-14, precision=yq.YQ_FP64,
+                  restart=4, maxiter=6)
+    pm.set_boundary_data(small["f"])
+    _, im = pm.solve(allow_noconv=True)
+    assert im["iterations"] == 6
+    assert im["matvecs_fp64"] >= 6
+
+
 def test_solve_forces_matches_solve_then_forces(small):
     """The fused final residual + gradient pass gives the separate calls' results."""
     kw = dict(tol=1e-9, precision=yq.YQ_MIXED)
@@ -205,7 +234,7 @@ def test_solve_forces_matches_solve_then_forces(small):
     Fa, Ta, Ea = pa.forces(sa, gamma=1.3)
     pf = _problem(small["parts"], small["P"], small["p"], **kw)
     pf.set_boundary_data(small["f"])
-    pf.lib.yq_profile_enable(pf.h, 1)
+    pf.lib.yq_profile_enable(pf.h, -1)
     sf, inf_, Ff, Tf, Ef = pf.solve_forces(gamma=1.3)
     nfu, _ = _phase(pf, 6)
     assert nfu >= 1                       # the fused pass ran
@@ -289,7 +318,7 @@ def test_medium_solve_residual_property(medium):
     assert np.abs(F.sum(0)).max() < 1e-2 * np.abs(F).max()   # tanh arc edges: see oracle pins
     assert E > 0
     # the fused final residual + gradient at full size gives the same forces
-    pm.lib.yq_profile_enable(pm.h, 1)
+    pm.lib.yq_profile_enable(pm.h, -1)
     sf, inf_, Ff, Tf, Ef = pm.solve_forces()
     assert _phase(pm, 6)[0] >= 1
     assert inf_["residual"] <= 1e-8
