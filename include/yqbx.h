@@ -121,7 +121,9 @@ int yq_set_stream(yq_problem* prob, void* hip_stream);
  * center_xy: host [2n] (x0,y0,x1,y1,...); angle: host [n] director angles;
  * semi_axes: host [2n] (A0,B0,A1,B1,...), A >= B > 0; kappa > 0.
  * Builds nodes, normals, weights, near lists and the FP64 QBX correction of
- * the operator and of its surface gradient.  Synchronous.
+ * the operator and of its surface gradient.  Returns once the geometry check
+ * is done; the rest of the build is queued on the problem's stream, ahead of
+ * every later call on the problem (host inputs may be reused on return).
  * YQ_EGEOM if a node of one particle lies inside another. */
 int yq_set_particles(yq_problem* prob, int32_t n, const double* center_xy, const double* angle,
                      const double* semi_axes, double kappa);

@@ -36,6 +36,23 @@ struct Timed {
   }
 };
 
+// Like Timed for a single kernel launch that records the two events itself
+// (hipExtLaunchKernel), so the timing adds no commands to the stream.
+struct LaunchTimed {
+  yq_problem* pb;
+  int phase;
+  hipEvent_t a = nullptr, b = nullptr;
+  LaunchTimed(yq_problem* p, int ph) : pb(p), phase(ph) {
+    if (pb->prof_mask & (1u << ph)) {
+      a = pb->event();
+      b = pb->event();
+    }
+  }
+  ~LaunchTimed() {
+    if (a) pb->ev[phase].push_back({a, b});
+  }
+};
+
 int fail(yq_problem* pb, const Error& e) {
   if (pb) pb->err = e.msg;
   g_last_error = e.msg;
@@ -125,16 +142,16 @@ void apply_op(yq_problem* pb, const double* sigma, double* out, int prec) {
   if (prec == YQ_MIXED) {
     pb->pack32(sigma);
     {
-      Timed t(pb, 1);
-      launch_far32(pb->far32(), pb->fp, pb->partial32.p, pb->stream, pb->stop_dev);
+      LaunchTimed t(pb, 1);
+      launch_far32(pb->far32(), pb->fp, pb->partial32.p, pb->stream, pb->stop_dev, t.a, t.b);
     }
     Timed t(pb, 2);
     launch_finish(g, win, pb->fp, nullptr, pb->partial32.p, pb->W.p, pb->xrow.p, pb->xpan.p,
                   pb->xvals.p, sigma, out, pb->stream);
   } else {
     {
-      Timed t(pb, 0);
-      launch_far64(g, sigma, pb->fp, pb->partial.p, pb->stream, pb->stop_dev);
+      LaunchTimed t(pb, 0);
+      launch_far64(g, sigma, pb->fp, pb->partial.p, pb->stream, pb->stop_dev, t.a, t.b);
     }
     Timed t(pb, 2);
     launch_finish(g, win, pb->fp, pb->partial.p, nullptr, pb->W.p, pb->xrow.p, pb->xpan.p,
@@ -276,11 +293,10 @@ int arnoldi_sync(yq_problem* pb, int prec, int maxsteps, double bnorm, double rt
 // the GPU does not idle while the host reads it.  When step j stops the cycle,
 // the already queued step j + 1 finds the device stop flag set: its far-field
 // launch and its Arnoldi kernel do nothing, and its cheap vector kernels write
-// only into unused Krylov storage.  Same results as arnoldi_sync up to the
-// rounding of the Givens arithmetic.
+// only into unused Krylov storage.  Also applies the cycle's update
+// x += V H^-1 g.  Same results as arnoldi_sync up to rounding.
 int arnoldi_pipelined(yq_problem* pb, int prec, int maxsteps, double beta, double bnorm,
-                      double rtol, std::vector<double>& H, std::vector<double>& gv, bool& done,
-                      GmresResult& R) {
+                      double rtol, double* x, bool& done, GmresResult& R) {
   const int64_t N = pb->N;
   const int m = pb->prm.restart;
   const int ldh = m + 1;
@@ -331,11 +347,9 @@ int arnoldi_pipelined(yq_problem* pb, int prec, int maxsteps, double beta, doubl
   R.matvecs += k;
   if (k > 0) {
     R.rel = hst[4 * (k - 1)];
-    std::vector<double> t((size_t)ldh * k + k);
-    YQ_HIP(hipMemcpy(t.data(), dH, (size_t)ldh * k * sizeof(double), hipMemcpyDeviceToHost));
-    YQ_HIP(hipMemcpy(t.data() + (size_t)ldh * k, dg, k * sizeof(double), hipMemcpyDeviceToHost));
-    std::copy(t.begin(), t.begin() + (size_t)ldh * k, H.begin());
-    std::copy(t.begin() + (size_t)ldh * k, t.end(), gv.begin());
+    // y = H^-1 g and x += V y on the device (queued; no host round trip)
+    launch_trisolve(dH, ldh, dg, k, pb->kred.p, s);
+    launch_update(x, V, N, k, pb->kred.p, 1.0, N, s);
   }
   done = stopped >= 0;
   return k;
@@ -343,8 +357,9 @@ int arnoldi_pipelined(yq_problem* pb, int prec, int maxsteps, double beta, doubl
 
 // Solves A x = b with restarted GMRES; x holds the initial guess (x_zero: 0).
 // The operator is applied with precision prec; Arnoldi is FP64 (CGS2).
+// bnorm_known: |b| when the caller has it (else negative).
 GmresResult gmres(yq_problem* pb, int prec, const double* b, double* x, bool x_zero, double rtol,
-                  int maxit) {
+                  int maxit, double bnorm_known = -1.0) {
   GmresResult R;
   const int64_t N = pb->N;
   const int m = pb->prm.restart;
@@ -353,7 +368,7 @@ GmresResult gmres(yq_problem* pb, int prec, const double* b, double* x, bool x_z
   double* w = pb->kw.p;
   double* r = pb->kr.p;
 
-  const double bnorm = std::sqrt(dot_host(pb, b, b));
+  const double bnorm = bnorm_known >= 0.0 ? bnorm_known : std::sqrt(dot_host(pb, b, b));
   if (bnorm == 0.0) {
     YQ_HIP(hipMemsetAsync(x, 0, N * sizeof(double), s));
     R.converged = true;
@@ -365,16 +380,19 @@ GmresResult gmres(yq_problem* pb, int prec, const double* b, double* x, bool x_z
   std::vector<double> H((m + 1) * m), gv(m + 1);
   bool first = true;
   while (true) {
-    // r = b - A x
+    // r = b - A x (b itself for a zero initial guess)
+    double beta;
     if (first && x_zero) {
-      YQ_HIP(hipMemcpyAsync(r, b, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+      r = const_cast<double*>(b);   // read only
+      beta = bnorm;
     } else {
+      r = pb->kr.p;
       apply_any(pb, x, w, prec);
       ++R.matvecs;
       launch_axpby(-1.0, w, 1.0, b, r, N, s);
+      beta = std::sqrt(dot_host(pb, r, r));
     }
     first = false;
-    const double beta = std::sqrt(dot_host(pb, r, r));
     R.rel = beta / bnorm;
     if (R.rel <= rtol) {
       R.converged = true;
@@ -387,18 +405,22 @@ GmresResult gmres(yq_problem* pb, int prec, const double* b, double* x, bool x_z
     gv[0] = beta;
     const int steps = std::min(m, maxit - R.iterations);
     bool done = false;
-    const int k = pipe ? arnoldi_pipelined(pb, prec, steps, beta, bnorm, rtol, H, gv, done, R)
-                       : arnoldi_sync(pb, prec, steps, bnorm, rtol, H, gv, done, R);
-    // y = H^-1 g (upper triangular), x += V y
-    std::vector<double> yv(k);
-    for (int i = k - 1; i >= 0; --i) {
-      double t = gv[i];
-      for (int c = i + 1; c < k; ++c) t -= H[(size_t)c * (m + 1) + i] * yv[c];
-      yv[i] = t / H[(size_t)i * (m + 1) + i];
-    }
-    if (k > 0) {
-      YQ_HIP(hipMemcpyAsync(pb->kred.p, yv.data(), k * sizeof(double), hipMemcpyHostToDevice, s));
-      launch_update(x, V, N, k, pb->kred.p, 1.0, N, s);
+    if (pipe) {
+      arnoldi_pipelined(pb, prec, steps, beta, bnorm, rtol, x, done, R);
+    } else {
+      const int k = arnoldi_sync(pb, prec, steps, bnorm, rtol, H, gv, done, R);
+      // y = H^-1 g (upper triangular), x += V y
+      std::vector<double> yv(k);
+      for (int i = k - 1; i >= 0; --i) {
+        double t = gv[i];
+        for (int c = i + 1; c < k; ++c) t -= H[(size_t)c * (m + 1) + i] * yv[c];
+        yv[i] = t / H[(size_t)i * (m + 1) + i];
+      }
+      if (k > 0) {
+        YQ_HIP(hipMemcpyAsync(pb->kred.p, yv.data(), k * sizeof(double), hipMemcpyHostToDevice,
+                              s));
+        launch_update(x, V, N, k, pb->kred.p, 1.0, N, s);
+      }
     }
     if (done) {
       R.converged = true;
@@ -592,9 +614,23 @@ int yq_set_particles(yq_problem* pb, int32_t n, const double* center_xy, const d
         nbp[p + 1] = (int)nbi.size();
       }
     }
-    upload(pb->pc, pb->h_pc, s);
-    upload_i(pb->nb_ptr, nbp, s);
-    upload_i(pb->nb_idx, nbi, s);
+    // host inputs go through pinned staging, so their copies are asynchronous; all
+    // of them complete before the geometry check below returns
+    {
+      const size_t b_pc = pb->h_pc.size() * sizeof(double);
+      const size_t b_np = nbp.size() * sizeof(int), b_ni = nbi.size() * sizeof(int);
+      pb->stage.fit(b_pc + b_np + b_ni + 16);
+      char* st = pb->stage.p;
+      std::memcpy(st, pb->h_pc.data(), b_pc);
+      std::memcpy(st + b_pc, nbp.data(), b_np);
+      if (b_ni) std::memcpy(st + b_pc + b_np, nbi.data(), b_ni);
+      pb->pc.fit(pb->h_pc.size());
+      pb->nb_ptr.fit(nbp.size());
+      pb->nb_idx.fit(std::max<size_t>(nbi.size(), 1));
+      YQ_HIP(hipMemcpyAsync(pb->pc.p, st, b_pc, hipMemcpyHostToDevice, s));
+      YQ_HIP(hipMemcpyAsync(pb->nb_ptr.p, st + b_pc, b_np, hipMemcpyHostToDevice, s));
+      if (b_ni) YQ_HIP(hipMemcpyAsync(pb->nb_idx.p, st + b_pc + b_np, b_ni, hipMemcpyHostToDevice, s));
+    }
 
     // a1: nodes, normals, weights; panel arclengths and bounding circles
     pb->x.alloc(N);
@@ -613,14 +649,24 @@ int yq_set_particles(yq_problem* pb, int32_t n, const double* center_xy, const d
                     pb->wny.p, s);
     launch_panel_stats(g, pb->panel_h.p, pb->pcx.p, pb->pcy.p, pb->pr.p, s);
 
-    // geometry check
+    // geometry check, and a3: extra near panels per node (count, then their row
+    // offsets by a device scan); one round trip brings back the check and the total
     pb->bad.alloc(1);
     YQ_HIP(hipMemsetAsync(pb->bad.p, 0, sizeof(int), s));
     launch_geom_check(g, pb->nb_ptr.p, pb->nb_idx.p, pb->bad.p, s);
-    int bad = 0;
-    YQ_HIP(hipMemcpyAsync(&bad, pb->bad.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    pb->xrow.alloc(N + 1);
+    DevBuf<int>& cnt = pb->ncnt;
+    cnt.fit(N);
+    launch_near_count(g, pb->prm.qbx_window, pb->prm.near_beta, pb->nb_ptr.p, pb->nb_idx.p,
+                      pb->pcx.p, pb->pcy.p, pb->pr.p, cnt.p, nullptr, nullptr, s);
+    launch_row_scan(cnt.p, N, pb->xrow.p, pb->scan_tmp, s);
+    pb->hflags.fit(2 * sizeof(int));
+    int* hfl = (int*)pb->hflags.p;
+    YQ_HIP(hipMemcpyAsync(hfl, pb->bad.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    YQ_HIP(hipMemcpyAsync(hfl + 1, pb->xrow.p + N, sizeof(int), hipMemcpyDeviceToHost, s));
     YQ_HIP(hipStreamSynchronize(s));
-    YQ_REQUIRE(bad == 0, YQ_EGEOM, "a node of one particle lies inside another particle");
+    YQ_REQUIRE(hfl[0] == 0, YQ_EGEOM, "a node of one particle lies inside another particle");
+    pb->x_total = hfl[1];
 
     // the FMM tree is built on the host from the node positions; their copy is
     // queued now so that the QBX build below runs while the tree is built
@@ -634,18 +680,7 @@ int yq_set_particles(yq_problem* pb, int32_t n, const double* center_xy, const d
       pb->fmm->download(pb->x.p, pb->y.p, pb->wnx.p, pb->wny.p, N, s);
     }
 
-    // a3: extra near panels (count, prefix sum, fill)
-    pb->xrow.alloc(N + 1);
-    DevBuf<int>& cnt = pb->ncnt;
-    cnt.fit(N);
-    launch_near_count(g, pb->prm.qbx_window, pb->prm.near_beta, pb->nb_ptr.p, pb->nb_idx.p,
-                      pb->pcx.p, pb->pcy.p, pb->pr.p, cnt.p, nullptr, nullptr, s);
-    std::vector<int> hc(N), hrow(N + 1, 0);
-    YQ_HIP(hipMemcpyAsync(hc.data(), cnt.p, N * sizeof(int), hipMemcpyDeviceToHost, s));
-    YQ_HIP(hipStreamSynchronize(s));
-    for (int64_t i = 0; i < N; ++i) hrow[i + 1] = hrow[i] + hc[i];
-    pb->x_total = hrow[N];
-    YQ_HIP(hipMemcpyAsync(pb->xrow.p, hrow.data(), (N + 1) * sizeof(int), hipMemcpyHostToDevice, s));
+    // a3: fill the extra near panel lists
     pb->xpan.fit(std::max<int64_t>(pb->x_total, 1));
     pb->xvals.fit(std::max<int64_t>(pb->x_total, 1) * Q);
     pb->xgvals.fit(std::max<int64_t>(pb->x_total, 1) * 2 * Q);
@@ -654,9 +689,12 @@ int yq_set_particles(yq_problem* pb, int32_t n, const double* center_xy, const d
                         pb->pcx.p, pb->pcy.p, pb->pr.p, nullptr, pb->xpan.p, pb->xrow.p, s);
 
     // a4: QBX correction (window) and oversampled rows (extra near panels)
-    upload(pb->Lqbx, interp_for(pb->consts, pb->prm.qbx_oversample), s);
-    upload(pb->Lnear, interp_for(pb->consts, pb->prm.near_oversample), s);
-    upload(pb->Lpot, interp_for(pb->consts, pb->prm.pot_oversample), s);
+    if (!pb->interp_ready) {   // depend on the parameters only
+      upload(pb->Lqbx, interp_for(pb->consts, pb->prm.qbx_oversample), s);
+      upload(pb->Lnear, interp_for(pb->consts, pb->prm.near_oversample), s);
+      upload(pb->Lpot, interp_for(pb->consts, pb->prm.pot_oversample), s);
+      pb->interp_ready = true;
+    }
     const size_t wsz = (size_t)(2 * pb->prm.qbx_window + 1) * Q * N;
     pb->W.alloc(wsz);
     pb->WGx.alloc(wsz);
@@ -705,7 +743,9 @@ int yq_set_particles(yq_problem* pb, int32_t n, const double* center_xy, const d
       pb->gy.alloc(N);
       ensure_krylov(pb);
     }
-    YQ_HIP(hipStreamSynchronize(s));
+    // the rest of the set-up stays queued on the problem's stream, ahead of any
+    // later work of the problem; batch members are read from the batch's stream
+    if (pb->batch_member) YQ_HIP(hipStreamSynchronize(s));
     pb->ready = true;
   });
 }
@@ -843,6 +883,7 @@ int solve_impl(yq_problem* pb, const double* sigma0, double* sigma, yq_solve_inf
     pb->grad_ready = false;
     fuse = fuse && pb->prm.precision == YQ_MIXED && !pb->fmm && !pb->fmm_hi;
     bool expect_last = false;  // the next residual is expected to meet the tolerance
+    double last_rel = -1.0;    // mixed: |f - A sigma| / |f| of the current residual r
     if (pb->prm.precision == YQ_FP64) {
       GmresResult R = gmres(pb, OP_RESID, pb->f.p, sigma, zero, pb->prm.tol, pb->prm.maxiter);
       inf.iterations = R.iterations;
@@ -857,10 +898,11 @@ int solve_impl(yq_problem* pb, const double* sigma0, double* sigma, yq_solve_inf
       const double fnorm = std::sqrt(dot_host(pb, pb->f.p, pb->f.p));
       int budget = pb->prm.maxiter;
       for (int outer = 0; outer < pb->prm.max_refine; ++outer) {
-        double rel;
+        double rel, rn;   // |r| / |f|, |r|
         if (outer == 0 && zero) {
           YQ_HIP(hipMemcpyAsync(r, pb->f.p, N * sizeof(double), hipMemcpyDeviceToDevice, s));
           rel = 1.0;
+          rn = fnorm;
         } else {
           if (fuse && expect_last)
             apply_resid_fused(pb, sigma, pb->kw.p);
@@ -868,7 +910,9 @@ int solve_impl(yq_problem* pb, const double* sigma0, double* sigma, yq_solve_inf
             apply_resid(pb, sigma, pb->kw.p);
           ++inf.matvecs_fp64;
           launch_axpby(-1.0, pb->kw.p, 1.0, pb->f.p, r, N, s);
-          rel = fnorm > 0.0 ? std::sqrt(dot_host(pb, r, r)) / fnorm : 0.0;
+          rn = std::sqrt(dot_host(pb, r, r));
+          rel = fnorm > 0.0 ? rn / fnorm : 0.0;
+          last_rel = rel;
         }
         r_current = true;
         if (rel <= pb->prm.tol) {
@@ -878,27 +922,32 @@ int solve_impl(yq_problem* pb, const double* sigma0, double* sigma, yq_solve_inf
         if (budget <= 0) break;
         ++inf.outer_steps;
         const double itol = std::max(pb->prm.inner_tol, 0.5 * pb->prm.tol / std::max(rel, 1e-300));
-        GmresResult R = gmres(pb, YQ_MIXED, r, delta.p, true, std::min(itol, 0.5), budget);
+        GmresResult R = gmres(pb, YQ_MIXED, r, delta.p, true, std::min(itol, 0.5), budget, rn);
         inf.iterations += R.iterations;
         inf.matvecs_fp32 += R.matvecs;
         budget -= R.iterations;
         launch_axpby(1.0, delta.p, 1.0, sigma, sigma, N, s);
         r_current = false;
+        last_rel = -1.0;
         pb->grad_ready = false;
         expect_last = rel * std::min(itol, 0.5) <= pb->prm.tol;
       }
     }
     // final FP64 residual (the refinement loop's last one when sigma has not moved since)
-    if (!r_current) {
-      if (fuse)
-        apply_resid_fused(pb, sigma, pb->kw.p);
-      else
-        apply_resid(pb, sigma, pb->kw.p);
-      ++inf.matvecs_fp64;
-      launch_axpby(-1.0, pb->kw.p, 1.0, pb->f.p, r, N, s);
+    if (r_current && last_rel >= 0.0) {
+      inf.residual = last_rel;
+    } else {
+      if (!r_current) {
+        if (fuse)
+          apply_resid_fused(pb, sigma, pb->kw.p);
+        else
+          apply_resid(pb, sigma, pb->kw.p);
+        ++inf.matvecs_fp64;
+        launch_axpby(-1.0, pb->kw.p, 1.0, pb->f.p, r, N, s);
+      }
+      const double fn = std::sqrt(dot_host(pb, pb->f.p, pb->f.p));
+      inf.residual = fn > 0.0 ? std::sqrt(dot_host(pb, r, r)) / fn : 0.0;
     }
-    const double fn = std::sqrt(dot_host(pb, pb->f.p, pb->f.p));
-    inf.residual = fn > 0.0 ? std::sqrt(dot_host(pb, r, r)) / fn : 0.0;
     if (pb->prm.precision == YQ_MIXED) conv = inf.residual <= pb->prm.tol;
     inf.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (info) *info = inf;

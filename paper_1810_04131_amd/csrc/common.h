@@ -177,6 +177,8 @@ void launch_geom_check(const GeomView& g, const int* nb_ptr, const int* nb_idx, 
 void launch_near_count(const GeomView& g, int win, double beta, const int* nb_ptr,
                        const int* nb_idx, const double* pcx, const double* pcy, const double* pr,
                        int* count, int* list, const int* offs, hipStream_t s);
+// row[0] = 0, row[i + 1] = count[0] + ... + count[i] (device; tmp: scan scratch)
+void launch_row_scan(const int* count, int64_t N, int* row, DevBuf<char>& tmp, hipStream_t s);
 
 void launch_qbx_build(const GeomView& g, const Consts& c, int p, int win, int nsub, double radius,
                       const double* L, double* W, double* WGx, double* WGy, hipStream_t s);
@@ -215,11 +217,13 @@ void launch_far32_geom(const double* x, const double* y, int64_t N, double kappa
                        double4* grp, float2* rel, hipStream_t s);
 void launch_pack32(const float2* rel, const double* wnx, const double* wny, const double* sigma,
                    int64_t N, double qc, float4* src, hipStream_t s);
-// stop: optional device flag; the launch does nothing when it is set
+// stop: optional device flag; the launch does nothing when it is set.  e0, e1:
+// optional events that the launch itself records at the kernel's start and end.
 void launch_far64(const GeomView& g, const double* sigma, const FarPlan& fp, double* partial,
-                  hipStream_t s, const int* stop = nullptr);
+                  hipStream_t s, const int* stop = nullptr, hipEvent_t e0 = nullptr,
+                  hipEvent_t e1 = nullptr);
 void launch_far32(const Far32View& v, const FarPlan& fp, float* partial, hipStream_t s,
-                  const int* stop = nullptr);
+                  const int* stop = nullptr, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 void launch_finish(const GeomView& g, int win, const FarPlan& fp, const double* partial64,
                    const float* partial32, const double* W, const int* xrow, const int* xpan,
                    const double* xvals, const double* sigma, double* out, hipStream_t s);
@@ -251,6 +255,8 @@ double sum_partials(const double* p, int nb);
 void launch_arnoldi(const double* part, int nb, int j, int ldh, double* H, double* cs, double* sn,
                     double* g, double* inv_hn, int* stop, double bnorm, double rtol,
                     double* status, hipStream_t s);
+// y[0..k) = R^-1 g, R the leading k x k upper triangle of H (device arrays)
+void launch_trisolve(const double* H, int ldh, const double* g, int k, double* y, hipStream_t s);
 // g[0] = beta, g[1..m] = 0, *stop = 0 (start of a GMRES cycle)
 void launch_gmres_init(double* g, int m, double beta, int* stop, hipStream_t s);
 void launch_update(double* w, const double* V, int64_t ld, int k, const double* h, double alpha,

@@ -12,6 +12,8 @@
 // partial sums go to partial[chunk * N + i]; the finish kernel adds them in a
 // fixed order (deterministic), scales, and applies the near correction.
 #include "bessel.h"
+#include <hip/hip_ext.h>
+
 #include "common.h"
 #include "farfield_core.h"
 
@@ -213,24 +215,59 @@ __global__ __launch_bounds__(FAR_BS) void far_fused64_kernel(GeomView g,
   }
 }
 
-// out_i = (kappa^2/2pi) sum_chunks partial + sum_window W sigma + sum_extra vals sigma
-__global__ void finish_kernel(GeomView g, int win, int chunks, const double* __restrict__ p64,
-                              const float* __restrict__ p32, const double* __restrict__ W,
-                              const int* __restrict__ xrow, const int* __restrict__ xpan,
-                              const double* __restrict__ xvals, const double* __restrict__ sigma,
-                              double* __restrict__ out) {
+// out_i = (kappa^2/2pi) sum_chunks partial + sum_window W sigma + sum_extra vals sigma.
+// Four lanes per node (a quad of one wavefront): lane q sums chunks q, q + 4, ...
+// and the terms m = 4q .. 4q + 3 of every window panel and extra panel; the quad
+// then combines its sums in a fixed order.  A node's quad is either wholly
+// inside [0, N) or wholly past it.
+__global__ __launch_bounds__(256) void finish_kernel(GeomView g, int win, int chunks,
+                                                     const double* __restrict__ p64,
+                                                     const float* __restrict__ p32,
+                                                     const double* __restrict__ W,
+                                                     const int* __restrict__ xrow,
+                                                     const int* __restrict__ xpan,
+                                                     const double* __restrict__ xvals,
+                                                     const double* __restrict__ sigma,
+                                                     double* __restrict__ out) {
   const int64_t N = g.N;
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t t = blockIdx.x * (int64_t)256 + threadIdx.x;
+  const int64_t i = t >> 2;
+  const int q = (int)(t & 3);
   if (i >= N) return;
   double s = 0.0;
   if (p64) {
-    for (int c = 0; c < chunks; ++c) s += p64[(int64_t)c * N + i];
+    for (int c = q; c < chunks; c += 4) s += p64[(int64_t)c * N + i];
   } else {
-    for (int c = 0; c < chunks; ++c) s += (double)p32[(int64_t)c * N + i];
+    for (int c = q; c < chunks; c += 4) s += (double)p32[(int64_t)c * N + i];
   }
-  s *= g.kappa * g.kappa / (2.0 * PI);
-  const double corr = win < 0 ? 0.0 : correction_row(i, N, g.P, win, W, xrow, xpan, xvals, sigma);
-  out[i] = s + corr;
+  double corr = 0.0;
+  if (win >= 0) {
+    const int P = g.P;
+    const int64_t pan = i / Q;
+    const int64_t pid = pan / P;
+    const int k = (int)(pan % P);
+    const int m0 = 4 * q;
+    for (int sl = 0; sl <= 2 * win; ++sl) {
+      int kj = (k + sl - win) % P;
+      if (kj < 0) kj += P;
+      const double* sg = sigma + (pid * P + kj) * Q + m0;
+      const double* wr = W + ((int64_t)sl * Q + m0) * N + i;
+#pragma unroll
+      for (int mm = 0; mm < 4; ++mm) corr = fma(wr[(int64_t)mm * N], sg[mm], corr);
+    }
+    if (xvals)
+      for (int e = xrow[i]; e < xrow[i + 1]; ++e) {
+        const double* sg = sigma + (int64_t)xpan[e] * Q + m0;
+        const double* vr = xvals + (int64_t)e * Q + m0;
+#pragma unroll
+        for (int mm = 0; mm < 4; ++mm) corr = fma(vr[mm], sg[mm], corr);
+      }
+  }
+  s += __shfl_xor(s, 1, 64);
+  s += __shfl_xor(s, 2, 64);
+  corr += __shfl_xor(corr, 1, 64);
+  corr += __shfl_xor(corr, 2, 64);
+  if (q == 0) out[i] = s * (g.kappa * g.kappa / (2.0 * PI)) + corr;
 }
 
 __global__ void finish_grad_kernel(GeomView g, int win, int chunks, const double* __restrict__ part,
@@ -277,9 +314,13 @@ __global__ void finish_grad_kernel(GeomView g, int win, int chunks, const double
 }
 
 void launch_far64(const GeomView& g, const double* sigma, const FarPlan& fp, double* partial,
-                  hipStream_t s, const int* stop) {
+                  hipStream_t s, const int* stop, hipEvent_t e0, hipEvent_t e1) {
   dim3 grid(fp.tblocks, fp.chunks);
-  far64_kernel<<<grid, FAR_BS, 0, s>>>(g, sigma, fp.chunk, partial, stop);
+  if (e0)
+    hipExtLaunchKernelGGL(far64_kernel, grid, dim3(FAR_BS), 0, s, e0, e1, 0, g, sigma, fp.chunk,
+                          partial, stop);
+  else
+    far64_kernel<<<grid, FAR_BS, 0, s>>>(g, sigma, fp.chunk, partial, stop);
   YQ_HIP(hipGetLastError());
 }
 
@@ -300,10 +341,14 @@ void launch_pack32(const float2* rel, const double* wnx, const double* wny, cons
 }
 
 void launch_far32(const Far32View& v, const FarPlan& fp, float* partial, hipStream_t s,
-                  const int* stop) {
+                  const int* stop, hipEvent_t e0, hipEvent_t e1) {
   YQ_REQUIRE(fp.chunk % FT == 0, YQ_EINVAL, "far32: chunk is not a multiple of the tile");
   dim3 grid(fp.tblocks, fp.chunks);
-  far32_kernel<<<grid, FAR_BS, 0, s>>>(v, fp.chunk, partial, stop);
+  if (e0)
+    hipExtLaunchKernelGGL(far32_kernel, grid, dim3(FAR_BS), 0, s, e0, e1, 0, v, fp.chunk, partial,
+                          stop);
+  else
+    far32_kernel<<<grid, FAR_BS, 0, s>>>(v, fp.chunk, partial, stop);
   YQ_HIP(hipGetLastError());
 }
 
@@ -324,7 +369,7 @@ void launch_far_grad64(const GeomView& g, const double* sigma, const FarPlan& fp
 void launch_finish(const GeomView& g, int win, const FarPlan& fp, const double* partial64,
                    const float* partial32, const double* W, const int* xrow, const int* xpan,
                    const double* xvals, const double* sigma, double* out, hipStream_t s) {
-  finish_kernel<<<(unsigned)((g.N + 255) / 256), 256, 0, s>>>(g, win, fp.chunks, partial64,
+  finish_kernel<<<(unsigned)((4 * g.N + 255) / 256), 256, 0, s>>>(g, win, fp.chunks, partial64,
                                                               partial32, W, xrow, xpan, xvals,
                                                               sigma, out);
   YQ_HIP(hipGetLastError());

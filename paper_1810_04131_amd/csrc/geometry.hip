@@ -3,6 +3,8 @@
 // panels are the composite Gauss-Legendre panels of section 5.
 #include <cmath>
 
+#include <hipcub/hipcub.hpp>
+
 #include "common.h"
 
 namespace yq {
@@ -258,6 +260,15 @@ void launch_near_count(const GeomView& g, int win, double beta, const int* nb_pt
   near_kernel<<<nblk(g.N, 128), 128, 0, s>>>(g, win, beta, nb_ptr, nb_idx, pcx, pcy, pr, count,
                                              list, offs);
   YQ_HIP(hipGetLastError());
+}
+
+void launch_row_scan(const int* count, int64_t N, int* row, DevBuf<char>& tmp, hipStream_t s) {
+  YQ_HIP(hipMemsetAsync(row, 0, sizeof(int), s));
+  if (N == 0) return;
+  size_t bytes = 0;
+  YQ_HIP(hipcub::DeviceScan::InclusiveSum(nullptr, bytes, count, row + 1, (int)N, s));
+  tmp.fit(std::max<size_t>(bytes, 1));
+  YQ_HIP(hipcub::DeviceScan::InclusiveSum(tmp.p, bytes, count, row + 1, (int)N, s));
 }
 
 }  // namespace yq

@@ -139,6 +139,24 @@ __global__ __launch_bounds__(64) void arnoldi_kernel(const double* __restrict__ 
   status[2] = (double)st;
 }
 
+// y = R^-1 g for the leading k x k upper triangle R of H (leading dimension
+// ldh), by back substitution: one wavefront, each row's dot product split over
+// the lanes and summed by a fixed butterfly.
+__global__ __launch_bounds__(64) void trisolve_kernel(const double* __restrict__ H, int ldh,
+                                                      const double* __restrict__ g, int k,
+                                                      double* __restrict__ y) {
+  __shared__ double ys[MAXR];
+  const int lane = threadIdx.x;
+  for (int i = k - 1; i >= 0; --i) {
+    double t = 0.0;
+    for (int c = i + 1 + lane; c < k; c += 64) t = fma(H[(int64_t)c * ldh + i], ys[c], t);
+    for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+    if (lane == 0) ys[i] = (g[i] - t) / H[(int64_t)i * ldh + i];
+    __syncthreads();
+  }
+  for (int i = lane; i < k; i += 64) y[i] = ys[i];
+}
+
 __global__ void gmres_init_kernel(double* __restrict__ g, int m, double beta,
                                   int* __restrict__ stop) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -152,6 +170,13 @@ void launch_arnoldi(const double* part, int nb, int j, int ldh, double* H, doubl
   YQ_REQUIRE(j >= 0 && j + 1 < ldh && j < MAXR, YQ_EINVAL, "arnoldi: column out of range");
   arnoldi_kernel<<<1, 64, 0, s>>>(part, nb, j, ldh, H, cs, sn, g, inv_hn, stop, bnorm, rtol,
                                   status);
+  YQ_HIP(hipGetLastError());
+}
+
+void launch_trisolve(const double* H, int ldh, const double* g, int k, double* y, hipStream_t s) {
+  if (k < 1) return;
+  YQ_REQUIRE(k <= MAXR && k < ldh, YQ_EINVAL, "trisolve: size out of range");
+  trisolve_kernel<<<1, 64, 0, s>>>(H, ldh, g, k, y);
   YQ_HIP(hipGetLastError());
 }
 

@@ -49,6 +49,10 @@ struct yq_problem {
   // Krylov workspace
   DevBuf<double> V, kw, kr, kd, kpart, kred;
   PinnedBuf hpart;   // host copy of Krylov partial dot products
+  PinnedBuf stage;   // set-up: staged host inputs
+  PinnedBuf hflags;  // set-up: geometry check flag and near-panel total
+  DevBuf<char> scan_tmp;
+  bool interp_ready = false;   // Lqbx, Lnear, Lpot uploaded
   // device-side Arnoldi bookkeeping (H, rotations, g, 1 / h_{j+1,j}, step status)
   DevBuf<double> gm;
   DevBuf<int> gstop;            // set when the GMRES cycle has stopped
