@@ -49,9 +49,11 @@ F32_CLASS = {"z8": 23, "z4": 25, "z2": 29, "general": 31}
 F64_CLASS = {"z8": 95, "z4": 103, "z2": 113, "general": 113}
 
 
-def far_class_mix(x, y, kappa):
+def far_class_mix(x, y, kappa, panels=False):
     """Fraction of the N^2 far-field pairs in each kernel class, from the same
-    bounding circles as the kernels (bounding-box centre, largest distance)."""
+    bounding circles as the kernels (bounding-box centre, largest distance):
+    per (64-target group, 256-source tile), and with panels=True (the FP32
+    kernel) per (group, 16-source panel) inside the tiles with close pairs."""
     import numpy as np
     n = len(x)
 
@@ -63,14 +65,30 @@ def far_class_mix(x, y, kappa):
             out.append((cx, cy, np.sqrt(((px - cx) ** 2 + (py - cy) ** 2).max()), len(px)))
         return np.array(out)
 
+    def gap(a, b):
+        return kappa * (np.hypot(a[:, None, 0] - b[None, :, 0], a[:, None, 1] - b[None, :, 1])
+                        - a[:, None, 2] - b[None, :, 2])
+
+    def split(z, w):
+        masks = {"z8": z >= 8, "z4": (z >= 4) & (z < 8), "z2": (z >= 2) & (z < 4),
+                 "general": z < 2}
+        return {c: float(w[m].sum()) for c, m in masks.items()}
+
     t, g = circles(256), circles(64)
-    zmin = kappa * (np.hypot(g[:, None, 0] - t[None, :, 0], g[:, None, 1] - t[None, :, 1])
-                    - g[:, None, 2] - t[None, :, 2])
-    w = g[:, None, 3] * t[None, :, 3]
-    tot = w.sum()
-    masks = {"z8": zmin >= 8, "z4": (zmin >= 4) & (zmin < 8), "z2": (zmin >= 2) & (zmin < 4),
-             "general": zmin < 2}
-    return {c: float(w[m].sum() / tot) for c, m in masks.items()}
+    zt = gap(g, t)
+    wt = g[:, None, 3] * t[None, :, 3]
+    tot = wt.sum()
+    if not panels:
+        return {c: v / tot for c, v in split(zt, wt).items()}
+    far = np.where(zt >= 2, zt, -1.0)
+    out = split(far, np.where(zt >= 2, wt, 0.0))
+    p = circles(16)
+    zp = gap(g, p)
+    wp = g[:, None, 3] * p[None, :, 3]
+    close = np.repeat(zt < 2, 16, axis=1)[:, :p.shape[0]]   # panels of the close tiles
+    for c, v in split(zp, np.where(close, wp, 0.0)).items():
+        out[c] += v
+    return {c: v / tot for c, v in out.items()}
 
 
 def flops_per_pair(mix, table):
@@ -551,9 +569,10 @@ def main():
     avg32 = ms32 / max(n32, 1) * 1e-3
     pairs = float(N) * (N - 1)
     nd = pb.nodes()
-    mix = far_class_mix(nd["x"].cpu().numpy(), nd["y"].cpu().numpy(), args.kappa)
+    xn, yn = nd["x"].cpu().numpy(), nd["y"].cpu().numpy()
+    mix = far_class_mix(xn, yn, args.kappa, panels=True)
     f32_pair = flops_per_pair(mix, F32_CLASS)
-    f64_pair = flops_per_pair(mix, F64_CLASS)
+    f64_pair = flops_per_pair(far_class_mix(xn, yn, args.kappa), F64_CLASS)
     achieved32 = f32_pair * pairs / avg32
     ms_step = t_all / args.steps * 1e3
 

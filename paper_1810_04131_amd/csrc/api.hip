@@ -140,7 +140,8 @@ void apply_op(yq_problem* pb, const double* sigma, double* out, int prec) {
     return;
   }
   if (prec == YQ_MIXED) {
-    pb->pack32(sigma);
+    if (pb->src_for != sigma) pb->pack32(sigma);   // else packed by the Arnoldi step
+    pb->src_for = nullptr;
     {
       LaunchTimed t(pb, 1);
       launch_far32(pb->far32(), pb->fp, pb->partial32.p, pb->stream, pb->stop_dev, t.a, t.b);
@@ -308,12 +309,12 @@ int arnoldi_pipelined(yq_problem* pb, int prec, int maxsteps, double beta, doubl
   double* dcs = dH + (size_t)ldh * m;            // [m]
   double* dsn = dcs + m;                         // [m]
   double* dg = dsn + m;                          // [m + 1]
-  double* dinv = dg + m + 1;                     // [1]
-  double* dst = dinv + 1;                        // [4 m] per-step status
+  double* dst = dg + m + 1 + 1;                  // [4 m] per-step status
   int* stop = pb->gstop.p;
   double* hst = (double*)pb->hstat.p;            // host copy of the status [4 m]
   launch_gmres_init(dg, m, beta, stop, s);
   pb->stop_dev = stop;
+  const bool pack = prec == YQ_MIXED && !pb->fmm;   // the next matvec packs FP32 sources
   int queued = 0, stopped = -1;
   for (int j = 0; j < maxsteps; ++j) {
     double* vj = V + (int64_t)j * N;
@@ -321,13 +322,17 @@ int arnoldi_pipelined(yq_problem* pb, int prec, int maxsteps, double beta, doubl
     apply_any(pb, vj, w, prec);
     const int64_t pc = (int64_t)(j + 1) * nb;
     double* kp = pb->kpart.p;
+    // CGS2; the second update also leaves the partials of |w|^2, and the Arnoldi
+    // step normalises the new basis vector (and packs its FP32 source records
+    // when the next application is the direct FP32 far field)
     launch_multidot(V, N, j + 1, w, N, kp, nb, s);
     launch_update_partial(w, V, N, j + 1, kp, nb, -1.0, N, s);
     launch_multidot(V, N, j + 1, w, N, kp + pc, nb, s);
-    launch_update_partial(w, V, N, j + 1, kp + pc, nb, -1.0, N, s);
-    launch_multidot(w, 0, 1, w, N, kp + 2 * pc, nb, s);
-    launch_arnoldi(kp, nb, j, ldh, dH, dcs, dsn, dg, dinv, stop, bnorm, rtol, dst + 4 * j, s);
-    launch_scale(w, dinv, vn, N, s);
+    launch_update_norm(w, V, N, j + 1, kp + pc, nb, -1.0, N, kp + 2 * pc, s);
+    launch_arnoldi_scale(kp, nb, kp + 2 * pc, j, ldh, dH, dcs, dsn, dg, stop, bnorm, rtol,
+                         dst + 4 * j, w, vn, N, pb->frel.p, pb->wnx.p, pb->wny.p,
+                         SQRT_LOG2E / pb->kappa, pack ? pb->fsrc.p : nullptr, s);
+    pb->src_for = pack ? vn : nullptr;
     YQ_HIP(hipMemcpyAsync(hst + 4 * j, dst + 4 * j, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
     YQ_HIP(hipEventRecord(pb->step_ev[j & 1], s));
     ++queued;
@@ -340,9 +345,18 @@ int arnoldi_pipelined(yq_problem* pb, int prec, int maxsteps, double beta, doubl
     }
   }
   pb->stop_dev = nullptr;
+  pb->src_for = nullptr;
   YQ_HIP(hipStreamSynchronize(s));
   if (stopped < 0 && queued > 0 && hst[4 * (queued - 1) + 2] != 0.0) stopped = queued - 1;
   const int k = stopped >= 0 ? stopped + 1 : queued;
+  // the far-field launches of the steps queued after the stop did nothing: their
+  // timing records (the phase's last ones) are dropped
+  const int ph = prec == YQ_MIXED ? 1 : 0;
+  for (int t = k; t < queued && (pb->prof_mask & (1u << ph)) && !pb->ev[ph].empty(); ++t) {
+    pb->pool.push_back(pb->ev[ph].back().first);
+    pb->pool.push_back(pb->ev[ph].back().second);
+    pb->ev[ph].pop_back();
+  }
   R.iterations += k;
   R.matvecs += k;
   if (k > 0) {
@@ -437,7 +451,7 @@ void ensure_krylov(yq_problem* pb) {
   pb->kw.reserve(N);
   pb->kr.reserve(N);
   pb->kd.reserve(N);
-  pb->kpart.reserve((size_t)krylov_blocks(N) * (2 * (m + 1) + 1));
+  pb->kpart.reserve((size_t)krylov_blocks(N) * (2 * (m + 1) + 1) + krylov_norm_blocks(N));
   pb->kred.reserve(2 * (m + 1) + 8);
   pb->gm.reserve((size_t)(m + 1) * m + 2 * m + (m + 1) + 1 + 4 * m);
   pb->gstop.reserve(1);
@@ -712,9 +726,11 @@ int yq_set_particles(yq_problem* pb, int32_t n, const double* center_xy, const d
     // FP32 far field: bounding circles, relative positions, source records
     pb->ftile.alloc((N + FT - 1) / FT);
     pb->fgrp.alloc((N + FG - 1) / FG);
+    pb->fpan.alloc(N / Q);
     pb->frel.alloc(N);
     pb->fsrc.alloc(N);
-    launch_far32_geom(pb->x.p, pb->y.p, N, kappa, pb->ftile.p, pb->fgrp.p, pb->frel.p, s);
+    launch_far32_geom(pb->x.p, pb->y.p, N, kappa, pb->ftile.p, pb->fgrp.p, pb->fpan.p, pb->frel.p,
+                      s);
 
     pb->fp = far_plan(N, N, 256, pb->far_want);
     if (use_fmm) {

@@ -204,6 +204,7 @@ struct Far32View {
   const double* y;
   const double4* tile; // per 256-node tile: centre x, y, radius
   const double4* grp;  // per 64-node group: centre x, y, radius
+  const double4* pan;  // per 16-node panel: centre x, y, radius
   const float4* src;   // per node, packed per matvec
   int64_t N;
   double s;            // kappa log2(e)
@@ -214,7 +215,7 @@ struct Far32View {
 };
 
 void launch_far32_geom(const double* x, const double* y, int64_t N, double kappa, double4* tile,
-                       double4* grp, float2* rel, hipStream_t s);
+                       double4* grp, double4* pan, float2* rel, hipStream_t s);
 void launch_pack32(const float2* rel, const double* wnx, const double* wny, const double* sigma,
                    int64_t N, double qc, float4* src, hipStream_t s);
 // stop: optional device flag; the launch does nothing when it is set.  e0, e1:
@@ -255,6 +256,19 @@ double sum_partials(const double* p, int nb);
 void launch_arnoldi(const double* part, int nb, int j, int ldh, double* H, double* cs, double* sn,
                     double* g, double* inv_hn, int* stop, double bnorm, double rtol,
                     double* status, hipStream_t s);
+// Blocks of the update_norm kernel (= the number of |w|^2 partials it writes)
+int krylov_norm_blocks(int64_t n);
+// launch_update_partial, and npart[b] = block b's sum of the new w_i^2
+void launch_update_norm(double* w, const double* V, int64_t ld, int k, const double* partial,
+                        int nb, double alpha, int64_t n, double* npart, hipStream_t s);
+// launch_arnoldi with |w|^2 from npart (krylov_norm_blocks(n) partials), fused
+// with vn = w / h_{j+1,j} and, when src is given, vn's FP32 source records
+// (rel, wnx, wny, qc as for launch_pack32)
+void launch_arnoldi_scale(const double* part, int nb, const double* npart, int j, int ldh,
+                          double* H, double* cs, double* sn, double* g, int* stop, double bnorm,
+                          double rtol, double* status, const double* w, double* vn, int64_t n,
+                          const float2* rel, const double* wnx, const double* wny, double qc,
+                          float4* src, hipStream_t s);
 // y[0..k) = R^-1 g, R the leading k x k upper triangle of H (device arrays)
 void launch_trisolve(const double* H, int ldh, const double* g, int k, double* y, hipStream_t s);
 // g[0] = beta, g[1..m] = 0, *stop = 0 (start of a GMRES cycle)

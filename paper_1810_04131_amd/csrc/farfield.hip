@@ -325,11 +325,12 @@ void launch_far64(const GeomView& g, const double* sigma, const FarPlan& fp, dou
 }
 
 void launch_far32_geom(const double* x, const double* y, int64_t N, double kappa, double4* tile,
-                       double4* grp, float2* rel, hipStream_t s) {
+                       double4* grp, double4* pan, float2* rel, hipStream_t s) {
   YQ_REQUIRE(N % Q == 0 && kappa > 0.0, YQ_EINVAL, "far32 geometry: N % 16 != 0 or kappa <= 0");
-  const int64_t nt = (N + FT - 1) / FT, ng = (N + FG - 1) / FG;
+  const int64_t nt = (N + FT - 1) / FT, ng = (N + FG - 1) / FG, np = N / Q;
   circles_kernel<<<(unsigned)((nt + 63) / 64), 64, 0, s>>>(x, y, N, FT, nt, tile);
   circles_kernel<<<(unsigned)((ng + 63) / 64), 64, 0, s>>>(x, y, N, FG, ng, grp);
+  circles_kernel<<<(unsigned)((np + 63) / 64), 64, 0, s>>>(x, y, N, Q, np, pan);
   rel32_kernel<<<(unsigned)((N + 255) / 256), 256, 0, s>>>(x, y, N, tile, kappa * LOG2E, rel);
   YQ_HIP(hipGetLastError());
 }

@@ -171,6 +171,10 @@ __device__ __forceinline__ float far32_near_tile(double xi, double yi, kptr<doub
 
 // Sum over sources [j0, j1) (j0 a multiple of 256, j1 - j0 a multiple of 16) for
 // target i of target group g (wavefront-uniform), in the scaling of far64_tile.
+// A source tile whose circle is far from the group's (kappa x gap >= 2) is one
+// segment of the class of that gap; a tile with close pairs is split into its
+// panels (16 sources), each classified by its own circle, so that only panels
+// near the group take the general path.
 __device__ __forceinline__ float far32_range(const Far32View& v, int64_t i, int64_t g,
                                              int64_t j0, int64_t j1) {
   const double xi = i < v.N ? v.x[i] : 0.0;
@@ -179,24 +183,39 @@ __device__ __forceinline__ float far32_range(const Far32View& v, int64_t i, int6
   const double gx = gc[0], gy = gc[1], gr = gc[2];
   kptr<float> src = as_k((const float*)v.src);
   float accf = 0.0f, accn = 0.0f;
-  for (int64_t jb = j0; jb < j1; jb += FT) {
-    kptr<double> tc = as_k((const double*)v.tile) + 4 * (jb / FT);
+  int64_t jb = j0;
+  while (jb < j1) {
+    const int64_t t = jb / FT;
+    kptr<double> tc = as_k((const double*)v.tile) + 4 * t;
     const double tcx = tc[0], tcy = tc[1];
+    const int64_t te = min(j1, (t + 1) * FT);   // end of this tile within the range
     const double cx = gx - tcx, cy = gy - tcy;
-    const double zmin = v.kappa * (sqrt(cx * cx + cy * cy) - gr - tc[2]);
-    const int nb = (int)min((int64_t)FT, j1 - jb);
-    if (zmin >= 2.0) {
-      const float tx = (float)((xi - tcx) * v.s), ty = (float)((yi - tcy) * v.s);
-      if (zmin >= 8.0)
-        accf = far32_far_tile<4, kH1Y_32_z8>(tx, ty, src + 4 * jb, nb, accf);
-      else if (zmin >= 4.0)
-        accf = far32_far_tile<5, kH1Y_32_z4>(tx, ty, src + 4 * jb, nb, accf);
+    const double zt = v.kappa * (sqrt(cx * cx + cy * cy) - gr - tc[2]);
+    const float tx = (float)((xi - tcx) * v.s), ty = (float)((yi - tcy) * v.s);
+    for (int64_t js = jb; js < te;) {
+      double z;
+      int len;
+      if (zt >= 2.0) {
+        z = zt;
+        len = (int)(te - js);
+      } else {
+        kptr<double> pc = as_k((const double*)v.pan) + 4 * (js / Q);
+        const double px = gx - pc[0], py = gy - pc[1];
+        z = v.kappa * (sqrt(px * px + py * py) - gr - pc[2]);
+        len = Q;
+      }
+      kptr<float> sp = src + 4 * js;
+      if (z >= 8.0)
+        accf = far32_far_tile<4, kH1Y_32_z8>(tx, ty, sp, len, accf);
+      else if (z >= 4.0)
+        accf = far32_far_tile<5, kH1Y_32_z4>(tx, ty, sp, len, accf);
+      else if (z >= 2.0)
+        accf = far32_far_tile<7, kH1Y_32>(tx, ty, sp, len, accf);
       else
-        accf = far32_far_tile<7, kH1Y_32>(tx, ty, src + 4 * jb, nb, accf);
-    } else {
-      accn = far32_near_tile(xi, yi, as_k(v.x) + jb, as_k(v.y) + jb, src + 4 * jb, nb, v.kap2,
-                             accn);
+        accn = far32_near_tile(xi, yi, as_k(v.x) + js, as_k(v.y) + js, sp, len, v.kap2, accn);
+      js += len;
     }
+    jb = te;
   }
   return fmaf(accn, v.nscale, accf);
 }

@@ -64,6 +64,32 @@ __global__ __launch_bounds__(KB) void update_partial_kernel(double* __restrict__
   w[i] = fma(alpha, s, w[i]);
 }
 
+// update_partial_kernel, and npart[block] = the block's sum of the new w_i^2
+// (a fixed-order block reduction): the partials of |w|^2 for the Arnoldi step.
+__global__ __launch_bounds__(KB) void update_norm_kernel(double* __restrict__ w,
+                                                         const double* __restrict__ V, int64_t ld,
+                                                         int kc, const double* __restrict__ partial,
+                                                         int nb, double alpha, int64_t n,
+                                                         double* __restrict__ npart) {
+  extern __shared__ double h[];   // [kc] coefficients, then [KB / 64] wavefront sums
+  for (int k = threadIdx.x; k < kc; k += KB) {
+    double t = 0.0;
+    for (int b = 0; b < nb; ++b) t += partial[(int64_t)k * nb + b];
+    h[k] = t;
+  }
+  __syncthreads();
+  const int64_t i = blockIdx.x * (int64_t)KB + threadIdx.x;
+  double v = 0.0;
+  if (i < n) {
+    double s = 0.0;
+    for (int k = 0; k < kc; ++k) s = fma(V[(int64_t)k * ld + i], h[k], s);
+    v = fma(alpha, s, w[i]);
+    w[i] = v;
+  }
+  const double t = block_sum_waves(v * v, h + kc);
+  if (threadIdx.x == 0) npart[blockIdx.x] = t;
+}
+
 // w[i] += alpha * sum_{k < kc} V[k][i] h[k]
 __global__ void update_kernel(double* __restrict__ w, const double* __restrict__ V, int64_t ld,
                               int kc, const double* __restrict__ h, double alpha, int64_t n) {
@@ -157,6 +183,81 @@ __global__ __launch_bounds__(64) void trisolve_kernel(const double* __restrict__
   for (int i = lane; i < k; i += 64) y[i] = ys[i];
 }
 
+// The Arnoldi step of arnoldi_kernel fused with the normalisation of the new
+// basis vector: |w| = h_{j+1,j} comes from the update kernel's block partials
+// npart[0..nbu) (every block sums them in the same order, so every block has the
+// same value); block 0 does the Hessenberg / Givens bookkeeping; every block
+// writes vn = w / h_{j+1,j} (0 at a breakdown) for its rows and, when src is
+// given, the FP32 source records of vn (as pack32_kernel).  The stop flag is read
+// once per block: a block that starts after block 0 has set it skips its rows,
+// which then belong to a basis vector that is never used.
+__global__ __launch_bounds__(KB) void arnoldi_scale_kernel(
+    const double* __restrict__ part, int nb, const double* __restrict__ npart, int nbu, int j,
+    int ldh, double* __restrict__ H, double* __restrict__ cs, double* __restrict__ sn,
+    double* __restrict__ g, int* __restrict__ stop, double bnorm, double rtol,
+    double* __restrict__ status, const double* __restrict__ w, double* __restrict__ vn, int64_t n,
+    const float2* __restrict__ rel, const double* __restrict__ wnx,
+    const double* __restrict__ wny, double qc, float4* __restrict__ src) {
+  __shared__ double hc[MAXR + 2];
+  __shared__ double h2s;
+  __shared__ int stopped;
+  if (threadIdx.x == 0) stopped = *stop;
+  __syncthreads();
+  if (stopped) return;   // uniform over the block
+  if (threadIdx.x < 64) {
+    double t = 0.0;
+    for (int q = threadIdx.x; q < nbu; q += 64) t += npart[q];
+    for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+    if (threadIdx.x == 0) h2s = t;
+  }
+  if (blockIdx.x == 0) {
+    const int64_t pc = (int64_t)(j + 1) * nb;
+    for (int i = threadIdx.x; i <= j; i += KB) {
+      double a = 0.0, b = 0.0;
+      for (int q = 0; q < nb; ++q) a += part[(int64_t)i * nb + q];
+      for (int q = 0; q < nb; ++q) b += part[pc + (int64_t)i * nb + q];
+      hc[i] = a + b;
+    }
+  }
+  __syncthreads();
+  const double hn = sqrt(fmax(h2s, 0.0));
+  const double inv = hn > 0.0 ? 1.0 / hn : 0.0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    hc[j + 1] = hn;
+    for (int i = 0; i < j; ++i) {
+      const double t = cs[i] * hc[i] + sn[i] * hc[i + 1];
+      hc[i + 1] = -sn[i] * hc[i] + cs[i] * hc[i + 1];
+      hc[i] = t;
+    }
+    const double den = hypot(hc[j], hc[j + 1]);
+    const double c = den > 0.0 ? hc[j] / den : 1.0;
+    const double sv = den > 0.0 ? hc[j + 1] / den : 0.0;
+    cs[j] = c;
+    sn[j] = sv;
+    hc[j] = den;
+    hc[j + 1] = 0.0;
+    const double gj = g[j];
+    g[j + 1] = -sv * gj;
+    g[j] = c * gj;
+    const double rel = fabs(sv * gj) / bnorm;
+    for (int i = 0; i <= j + 1; ++i) H[(int64_t)j * ldh + i] = hc[i];
+    const int st = (rel <= rtol || hn == 0.0) ? 1 : 0;
+    status[0] = rel;
+    status[1] = hn;
+    status[2] = (double)st;
+    *stop = st;
+  }
+  const int64_t i = blockIdx.x * (int64_t)KB + threadIdx.x;
+  if (i >= n) return;
+  const double v = w[i] * inv;
+  vn[i] = v;
+  if (src) {
+    const double sc = v * qc;
+    const float2 r = rel[i];
+    src[i] = make_float4(r.x, r.y, (float)(wnx[i] * sc), (float)(wny[i] * sc));
+  }
+}
+
 __global__ void gmres_init_kernel(double* __restrict__ g, int m, double beta,
                                   int* __restrict__ stop) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -177,6 +278,29 @@ void launch_trisolve(const double* H, int ldh, const double* g, int k, double* y
   if (k < 1) return;
   YQ_REQUIRE(k <= MAXR && k < ldh, YQ_EINVAL, "trisolve: size out of range");
   trisolve_kernel<<<1, 64, 0, s>>>(H, ldh, g, k, y);
+  YQ_HIP(hipGetLastError());
+}
+
+int krylov_norm_blocks(int64_t n) { return (int)((n + KB - 1) / KB); }
+
+void launch_update_norm(double* w, const double* V, int64_t ld, int k, const double* partial,
+                        int nb, double alpha, int64_t n, double* npart, hipStream_t s) {
+  YQ_REQUIRE(k >= 1, YQ_EINVAL, "update_norm: no columns");
+  update_norm_kernel<<<(unsigned)krylov_norm_blocks(n), KB, (k + KB / 64) * sizeof(double), s>>>(
+      w, V, ld, k, partial, nb, alpha, n, npart);
+  YQ_HIP(hipGetLastError());
+}
+
+void launch_arnoldi_scale(const double* part, int nb, const double* npart, int j, int ldh,
+                          double* H, double* cs, double* sn, double* g, int* stop, double bnorm,
+                          double rtol, double* status, const double* w, double* vn, int64_t n,
+                          const float2* rel, const double* wnx, const double* wny, double qc,
+                          float4* src, hipStream_t s) {
+  YQ_REQUIRE(j >= 0 && j + 1 < ldh && j < MAXR, YQ_EINVAL, "arnoldi: column out of range");
+  const int nbu = krylov_norm_blocks(n);
+  arnoldi_scale_kernel<<<(unsigned)nbu, KB, 0, s>>>(part, nb, npart, nbu, j, ldh, H, cs, sn, g,
+                                                    stop, bnorm, rtol, status, w, vn, n, rel, wnx,
+                                                    wny, qc, src);
   YQ_HIP(hipGetLastError());
 }
 

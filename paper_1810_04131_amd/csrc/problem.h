@@ -29,7 +29,7 @@ struct yq_problem {
   DevBuf<double> pc, x, y, nx, ny, w, wnx, wny, panel_h, pcx, pcy, pr;
   // FP32 far field: tile / group bounding circles, scaled relative positions,
   // per-matvec packed sources
-  DevBuf<double4> ftile, fgrp;
+  DevBuf<double4> ftile, fgrp, fpan;
   DevBuf<float2> frel;
   DevBuf<float4> fsrc;
   DevBuf<double> pot_partial;
@@ -59,6 +59,7 @@ struct yq_problem {
   PinnedBuf hstat;              // host copy of the step status
   hipEvent_t step_ev[2] = {nullptr, nullptr};
   const int* stop_dev = nullptr;   // passed to the far-field launches while set
+  const double* src_for = nullptr; // fsrc already holds the FP32 records of this vector
   DevBuf<double> gx, gy, en;
   DevBuf<double> delta;   // refinement correction
   bool grad_ready = false;  // gpartial holds the direct gradient far field of the solve's sigma
@@ -96,6 +97,7 @@ struct yq_problem {
     v.y = y.p;
     v.tile = ftile.p;
     v.grp = fgrp.p;
+    v.pan = fpan.p;
     v.src = fsrc.p;
     v.N = N;
     v.s = kappa * LOG2E;
