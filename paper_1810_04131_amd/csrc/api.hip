@@ -125,7 +125,7 @@ std::vector<double> interp_for(const Consts& c, int nsub) {
 // enabled; the FP64 operator is always the exact direct sum.
 void far_fmm(yq_problem* pb, const double* sigma) {
   Timed t(pb, 1);
-  pb->fmm->apply(sigma, pb->partial.p, true, pb->tab.p, pb->stream);
+  pb->fmm->apply(sigma, pb->partial.p, true, pb->tab.p, pb->stream, pb->stop_dev);
 }
 
 void apply_op(yq_problem* pb, const double* sigma, double* out, int prec) {
@@ -170,7 +170,7 @@ void apply_resid(yq_problem* pb, const double* sigma, double* out) {
   }
   {
     Timed t(pb, 0);
-    pb->fmm_hi->apply(sigma, pb->partial.p, false, pb->tab.p, pb->stream);
+    pb->fmm_hi->apply(sigma, pb->partial.p, false, pb->tab.p, pb->stream, pb->stop_dev);
   }
   FarPlan one{pb->fp.tblocks, 1, (int)pb->N};
   Timed t(pb, 2);
@@ -220,82 +220,14 @@ struct GmresResult {
   double rel = 0.0;  // residual estimate relative to ||b||
 };
 
-// Whether the operator of precision prec is the direct far field, whose kernels
-// honour the GMRES stop flag (the FMM's do not).
-bool direct_operator(const yq_problem* pb, int prec) {
-  if (prec == YQ_MIXED) return !pb->fmm;
-  if (prec == OP_RESID) return !pb->fmm_hi;
-  return true;
-}
-
-// Arnoldi of one GMRES cycle, bookkeeping on the host: after each step the
-// stream is synchronised and the Hessenberg column, its Givens rotation and the
-// residual estimate are done here.  Returns the number of steps k; H (host,
-// leading dimension m + 1) and gv hold the rotated columns and right-hand side.
-int arnoldi_sync(yq_problem* pb, int prec, int maxsteps, double bnorm, double rtol,
-                 std::vector<double>& H, std::vector<double>& gv, bool& done, GmresResult& R) {
-  const int64_t N = pb->N;
-  const int m = pb->prm.restart;
-  const int nb = krylov_blocks(N);
-  hipStream_t s = pb->stream;
-  double* V = pb->V.p;
-  double* w = pb->kw.p;
-  std::vector<double> cs(m), sn(m);
-  const double* hp = (const double*)pb->hpart.p;
-  int j = 0;
-  for (; j < maxsteps; ++j) {
-    double* vj = V + (int64_t)j * N;
-    double* vn = V + (int64_t)(j + 1) * N;
-    apply_any(pb, vj, w, prec);
-    ++R.matvecs;
-    // classical Gram-Schmidt, twice; the per-block partial products of both
-    // passes and of |w|^2 go to the host in one copy, and each update kernel
-    // sums its pass's partials itself in the host's order
-    const int64_t pc = (int64_t)(j + 1) * nb;
-    double* kp = pb->kpart.p;
-    launch_multidot(V, N, j + 1, w, N, kp, nb, s);
-    launch_update_partial(w, V, N, j + 1, kp, nb, -1.0, N, s);
-    launch_multidot(V, N, j + 1, w, N, kp + pc, nb, s);
-    launch_update_partial(w, V, N, j + 1, kp + pc, nb, -1.0, N, s);
-    launch_multidot(w, 0, 1, w, N, kp + 2 * pc, nb, s);
-    YQ_HIP(hipMemcpyAsync((void*)hp, kp, (2 * pc + nb) * sizeof(double), hipMemcpyDeviceToHost,
-                          s));
-    YQ_HIP(hipStreamSynchronize(s));
-    ++R.iterations;
-    double* hc = &H[(size_t)j * (m + 1)];  // column j, rows 0..j+1
-    for (int i = 0; i <= j; ++i)
-      hc[i] = sum_partials(hp + (int64_t)i * nb, nb) + sum_partials(hp + pc + (int64_t)i * nb, nb);
-    const double hn = std::sqrt(std::max(sum_partials(hp + 2 * pc, nb), 0.0));
-    hc[j + 1] = hn;
-    if (hn > 0.0) launch_axpby(1.0 / hn, w, 0.0, nullptr, vn, N, s);
-    for (int i = 0; i < j; ++i) {
-      const double t = cs[i] * hc[i] + sn[i] * hc[i + 1];
-      hc[i + 1] = -sn[i] * hc[i] + cs[i] * hc[i + 1];
-      hc[i] = t;
-    }
-    const double den = std::hypot(hc[j], hc[j + 1]);
-    cs[j] = den > 0.0 ? hc[j] / den : 1.0;
-    sn[j] = den > 0.0 ? hc[j + 1] / den : 0.0;
-    hc[j] = den;
-    hc[j + 1] = 0.0;
-    gv[j + 1] = -sn[j] * gv[j];
-    gv[j] = cs[j] * gv[j];
-    R.rel = std::fabs(gv[j + 1]) / bnorm;
-    if (R.rel <= rtol || hn == 0.0) {
-      done = true;
-      return j + 1;
-    }
-  }
-  return j;
-}
-
 // Arnoldi of one GMRES cycle with the bookkeeping on the device (arnoldi
 // kernel): the host queues step j + 1 before it waits for step j's status, so
 // the GPU does not idle while the host reads it.  When step j stops the cycle,
 // the already queued step j + 1 finds the device stop flag set: its far-field
 // launch and its Arnoldi kernel do nothing, and its cheap vector kernels write
 // only into unused Krylov storage.  Also applies the cycle's update
-// x += V H^-1 g.  Same results as arnoldi_sync up to rounding.
+// x += V H^-1 g.  Every far-field path (direct kernels, both FMMs) honours the
+// stop flag.
 int arnoldi_pipelined(yq_problem* pb, int prec, int maxsteps, double beta, double bnorm,
                       double rtol, double* x, bool& done, GmresResult& R) {
   const int64_t N = pb->N;
@@ -390,8 +322,6 @@ GmresResult gmres(yq_problem* pb, int prec, const double* b, double* x, bool x_z
   }
   if (x_zero) YQ_HIP(hipMemsetAsync(x, 0, N * sizeof(double), s));
 
-  const bool pipe = direct_operator(pb, prec);
-  std::vector<double> H((m + 1) * m), gv(m + 1);
   bool first = true;
   while (true) {
     // r = b - A x (b itself for a zero initial guess)
@@ -415,27 +345,9 @@ GmresResult gmres(yq_problem* pb, int prec, const double* b, double* x, bool x_z
     if (R.iterations >= maxit) return R;
     ++R.cycles;
     launch_axpby(1.0 / beta, r, 0.0, nullptr, V, N, s);
-    std::fill(gv.begin(), gv.end(), 0.0);
-    gv[0] = beta;
     const int steps = std::min(m, maxit - R.iterations);
     bool done = false;
-    if (pipe) {
-      arnoldi_pipelined(pb, prec, steps, beta, bnorm, rtol, x, done, R);
-    } else {
-      const int k = arnoldi_sync(pb, prec, steps, bnorm, rtol, H, gv, done, R);
-      // y = H^-1 g (upper triangular), x += V y
-      std::vector<double> yv(k);
-      for (int i = k - 1; i >= 0; --i) {
-        double t = gv[i];
-        for (int c = i + 1; c < k; ++c) t -= H[(size_t)c * (m + 1) + i] * yv[c];
-        yv[i] = t / H[(size_t)i * (m + 1) + i];
-      }
-      if (k > 0) {
-        YQ_HIP(hipMemcpyAsync(pb->kred.p, yv.data(), k * sizeof(double), hipMemcpyHostToDevice,
-                              s));
-        launch_update(x, V, N, k, pb->kred.p, 1.0, N, s);
-      }
-    }
+    arnoldi_pipelined(pb, prec, steps, beta, bnorm, rtol, x, done, R);
     if (done) {
       R.converged = true;
       return R;
@@ -456,7 +368,7 @@ void ensure_krylov(yq_problem* pb) {
   pb->gm.reserve((size_t)(m + 1) * m + 2 * m + (m + 1) + 1 + 4 * m);
   pb->gstop.reserve(1);
   pb->hstat.fit((size_t)4 * m * sizeof(double));
-  pb->hpart.fit((size_t)(2 * (m + 1) + 1) * krylov_blocks(N) * sizeof(double));
+  pb->hpart.fit((size_t)krylov_blocks(N) * sizeof(double));
   for (auto& e : pb->step_ev)
     if (!e) YQ_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
 }
@@ -715,9 +627,17 @@ int yq_set_particles(yq_problem* pb, int32_t n, const double* center_xy, const d
     pb->WGy.alloc(wsz);
     {
       Timed t(pb, 4);
-      launch_qbx_build(g, pb->consts, pb->prm.qbx_order, pb->prm.qbx_window,
-                       pb->prm.qbx_oversample, pb->prm.qbx_radius, pb->Lqbx.p, pb->W.p, pb->WGx.p,
-                       pb->WGy.p, s);
+      const int qs = pb->prm.qbx_oversample;
+      const size_t nq = (size_t)N * qs;
+      pb->qfx.fit(nq);
+      pb->qfy.fit(nq);
+      pb->qfwx.fit(nq);
+      pb->qfwy.fit(nq);
+      launch_pot_fine(g, pb->consts, qs,
+                      PotFine{qs, pb->qfx.p, pb->qfy.p, pb->qfwx.p, pb->qfwy.p, nullptr}, s);
+      launch_qbx_build(g, pb->prm.qbx_order, pb->prm.qbx_window, qs, pb->prm.qbx_radius,
+                       pb->Lqbx.p, pb->qfx.p, pb->qfy.p, pb->qfwx.p, pb->qfwy.p, pb->W.p,
+                       pb->WGx.p, pb->WGy.p, s);
     }
     if (pb->x_total > 0)
       launch_near_rows(g, pb->consts, pb->prm.near_oversample, pb->Lnear.p, pb->xrow.p,

@@ -180,8 +180,11 @@ void launch_near_count(const GeomView& g, int win, double beta, const int* nb_pt
 // row[0] = 0, row[i + 1] = count[0] + ... + count[i] (device; tmp: scan scratch)
 void launch_row_scan(const int* count, int64_t N, int* row, DevBuf<char>& tmp, hipStream_t s);
 
-void launch_qbx_build(const GeomView& g, const Consts& c, int p, int win, int nsub, double radius,
-                      const double* L, double* W, double* WGx, double* WGy, hipStream_t s);
+// fx, fy, fwx, fwy: the oversampled points of every panel (nsub sub-panels), as
+// built by launch_pot_fine
+void launch_qbx_build(const GeomView& g, int p, int win, int nsub, double radius, const double* L,
+                      const double* fx, const double* fy, const double* fwx, const double* fwy,
+                      double* W, double* WGx, double* WGy, hipStream_t s);
 void launch_near_rows(const GeomView& g, const Consts& c, int nsub, const double* L,
                       const int* row_ptr, const int* panels, double* vals, double* gvals,
                       hipStream_t s);
@@ -246,24 +249,19 @@ void launch_update_partial(double* w, const double* V, int64_t ld, int k, const 
                            int nb, double alpha, int64_t n, hipStream_t s);
 // p[0] + p[1] + ... + p[nb - 1] in that order, on the host (the update kernel's order)
 double sum_partials(const double* p, int nb);
-// One Arnoldi step's bookkeeping on the device (the host-side GMRES does the same
-// on the host): Hessenberg column j (leading dimension ldh) from the partials of
-// the two Gram-Schmidt passes and of |w|^2 at part, the earlier Givens rotations
-// (cs, sn) applied to it, the new rotation, g updated, inv_hn = 1 / h_{j+1,j}
-// (0 at a breakdown), *stop set when |g_{j+1}| / bnorm <= rtol or at a breakdown,
-// and status = (|g_{j+1}| / bnorm, h_{j+1,j}, stop).  Nothing happens when *stop
-// is already set.
-void launch_arnoldi(const double* part, int nb, int j, int ldh, double* H, double* cs, double* sn,
-                    double* g, double* inv_hn, int* stop, double bnorm, double rtol,
-                    double* status, hipStream_t s);
 // Blocks of the update_norm kernel (= the number of |w|^2 partials it writes)
 int krylov_norm_blocks(int64_t n);
 // launch_update_partial, and npart[b] = block b's sum of the new w_i^2
 void launch_update_norm(double* w, const double* V, int64_t ld, int k, const double* partial,
                         int nb, double alpha, int64_t n, double* npart, hipStream_t s);
-// launch_arnoldi with |w|^2 from npart (krylov_norm_blocks(n) partials), fused
-// with vn = w / h_{j+1,j} and, when src is given, vn's FP32 source records
-// (rel, wnx, wny, qc as for launch_pack32)
+// One Arnoldi step on the device: Hessenberg column j (leading dimension ldh)
+// from the partials of the two Gram-Schmidt passes at part (nb per column),
+// h_{j+1,j} = |w| from npart (krylov_norm_blocks(n) partials), the earlier Givens
+// rotations (cs, sn) applied, the new rotation, g updated, *stop set when
+// |g_{j+1}| / bnorm <= rtol or at a breakdown, status = (|g_{j+1}| / bnorm,
+// h_{j+1,j}, stop); fused with vn = w / h_{j+1,j} (0 at a breakdown) and, when src
+// is given, vn's FP32 source records (rel, wnx, wny, qc as for launch_pack32).
+// Nothing happens when *stop is already set.
 void launch_arnoldi_scale(const double* part, int nb, const double* npart, int j, int ldh,
                           double* H, double* cs, double* sn, double* g, int* stop, double bnorm,
                           double rtol, double* status, const double* w, double* vn, int64_t n,
@@ -277,7 +275,6 @@ void launch_update(double* w, const double* V, int64_t ld, int k, const double* 
                    int64_t n, hipStream_t s);
 void launch_axpby(double a, const double* x, double b, const double* y, double* out, int64_t n,
                   hipStream_t s);
-void launch_scale(const double* x, const double* inv, double* out, int64_t n, hipStream_t s);
 
 // post-processing (post.hip)
 void launch_forces(const GeomView& g, const double* f, const double* gx, const double* gy,

@@ -68,14 +68,16 @@ struct Fmm {
   void set_order(int q, const double* tab, hipStream_t s);
   void copy_tree(const Fmm& o, int q, const double* tab, hipStream_t s);
   // partial[i] = (2 pi / kappa^2) * far field at node i (the far-field kernels' scaling)
-  void m2l_mfma(hipStream_t s);
-  void m2l_mfma32(hipStream_t s);
+  // stop (optional device flag): the heavy kernels do nothing once it is set
+  void m2l_mfma(hipStream_t s, const int* stop = nullptr);
+  void m2l_mfma32(hipStream_t s, const int* stop = nullptr);
   void tree_mfma(bool gather, int l, hipStream_t s);
-  void expansions(const double* sigma, hipStream_t s, bool m2l32 = false);
+  void expansions(const double* sigma, hipStream_t s, bool m2l32 = false,
+                  const int* stop = nullptr);
   // gpart[i], gpart[N + i] = (2 pi / kappa^2) * gradient of the far field at node i (FP64)
   void apply_grad(const double* sigma, double* gpart, const double* tab, hipStream_t s);
   void apply(const double* sigma, double* partial, bool p2p_fp32, const double* tab,
-             hipStream_t s);
+             hipStream_t s, const int* stop = nullptr);
 };
 
 }  // namespace yq

@@ -203,7 +203,9 @@ __global__ __launch_bounds__(64) void p2m_kernel(int p, int use_col, double kapp
                                                  const double* __restrict__ ys,
                                                  const double* __restrict__ qx,
                                                  const double* __restrict__ qy,
-                                                 double2* __restrict__ M) {
+                                                 double2* __restrict__ M,
+                                                 const int* __restrict__ stop) {
+  if (stop && *stop) return;   // a GMRES step queued after the stop
   extern __shared__ double itab[];   // [(p + 2) * 64]: scaled I_n, one column per lane
   const int lane = threadIdx.x;
   const int b = blockIdx.x;
@@ -423,7 +425,9 @@ struct M2LLevels {
 template <int RT>
 __global__ __launch_bounds__(256) void m2l_mfma_kernel(int p, const int2* __restrict__ tiles,
                                                        M2LLevels lv, const double* __restrict__ amat,
-                                                       int64_t level_stride) {
+                                                       int64_t level_stride,
+                                                       const int* __restrict__ stop) {
+  if (stop && *stop) return;
   constexpr int R = RT * 16, KS = R / 4, NI = 10;
   __shared__ dbl4 red[3 * 64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -486,7 +490,9 @@ __global__ __launch_bounds__(256) void m2l_mfma32_kernel(int p, const int2* __re
                                                          M2LLevels lv,
                                                          const float* __restrict__ amat32,
                                                          int64_t level_stride,
-                                                         const double* __restrict__ msc) {
+                                                         const double* __restrict__ msc,
+                                                         const int* __restrict__ stop) {
+  if (stop && *stop) return;
   constexpr int R = RT * 16, KS = R / 4, NI = 10;
   __shared__ dbl4 red[3 * 64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -619,7 +625,9 @@ __global__ __launch_bounds__(FB) void l2p_p2p_kernel(int p, double kappa, int us
                                                      const double* __restrict__ qy,
                                                      const int* __restrict__ perm,
                                                      const double* __restrict__ tab,
-                                                     double* __restrict__ partial) {
+                                                     double* __restrict__ partial,
+                                                     const int* __restrict__ stop) {
+  if (stop && *stop) return;
   extern __shared__ double sh[];
   double2* sxy = reinterpret_cast<double2*>(sh);            // [FB]
   double2* sq = sxy + FB;                                   // [FB] (FP64 strengths)
@@ -1238,7 +1246,7 @@ void Fmm::copy_tree(const Fmm& o, int q, const double* tab, hipStream_t s) {
   set_order(q, tab, s);
 }
 
-void Fmm::m2l_mfma(hipStream_t s) {
+void Fmm::m2l_mfma(hipStream_t s, const int* stop) {
   M2LLevels a{};
   for (int l = 2; l <= depth; ++l) {
     a.ild[l] = lv[l].ild.p;
@@ -1251,18 +1259,18 @@ void Fmm::m2l_mfma(hipStream_t s) {
   if (g == 0) return;
   const int64_t ls = (int64_t)49 * R16 * R16;
   switch (RT) {
-    case 1: m2l_mfma_kernel<1><<<g, 256, 0, s>>>(p, m2l_tiles.p, a, amat.p, ls); break;
-    case 2: m2l_mfma_kernel<2><<<g, 256, 0, s>>>(p, m2l_tiles.p, a, amat.p, ls); break;
-    case 3: m2l_mfma_kernel<3><<<g, 256, 0, s>>>(p, m2l_tiles.p, a, amat.p, ls); break;
-    case 4: m2l_mfma_kernel<4><<<g, 256, 0, s>>>(p, m2l_tiles.p, a, amat.p, ls); break;
-    case 5: m2l_mfma_kernel<5><<<g, 256, 0, s>>>(p, m2l_tiles.p, a, amat.p, ls); break;
-    case 6: m2l_mfma_kernel<6><<<g, 256, 0, s>>>(p, m2l_tiles.p, a, amat.p, ls); break;
-    default: m2l_mfma_kernel<7><<<g, 256, 0, s>>>(p, m2l_tiles.p, a, amat.p, ls); break;
+    case 1: m2l_mfma_kernel<1><<<g, 256, 0, s>>>(p, m2l_tiles.p, a, amat.p, ls, stop); break;
+    case 2: m2l_mfma_kernel<2><<<g, 256, 0, s>>>(p, m2l_tiles.p, a, amat.p, ls, stop); break;
+    case 3: m2l_mfma_kernel<3><<<g, 256, 0, s>>>(p, m2l_tiles.p, a, amat.p, ls, stop); break;
+    case 4: m2l_mfma_kernel<4><<<g, 256, 0, s>>>(p, m2l_tiles.p, a, amat.p, ls, stop); break;
+    case 5: m2l_mfma_kernel<5><<<g, 256, 0, s>>>(p, m2l_tiles.p, a, amat.p, ls, stop); break;
+    case 6: m2l_mfma_kernel<6><<<g, 256, 0, s>>>(p, m2l_tiles.p, a, amat.p, ls, stop); break;
+    default: m2l_mfma_kernel<7><<<g, 256, 0, s>>>(p, m2l_tiles.p, a, amat.p, ls, stop); break;
   }
   YQ_HIP(hipGetLastError());
 }
 
-void Fmm::m2l_mfma32(hipStream_t s) {
+void Fmm::m2l_mfma32(hipStream_t s, const int* stop) {
   M2LLevels a{};
   for (int l = 2; l <= depth; ++l) {
     a.ild[l] = lv[l].ild.p;
@@ -1275,13 +1283,13 @@ void Fmm::m2l_mfma32(hipStream_t s) {
   if (g == 0) return;
   const int64_t ls = (int64_t)49 * R16 * R16;
   switch (RT) {
-    case 1: m2l_mfma32_kernel<1><<<g, 256, 0, s>>>(p, m2l_tiles.p, a, amat32.p, ls, msc.p); break;
-    case 2: m2l_mfma32_kernel<2><<<g, 256, 0, s>>>(p, m2l_tiles.p, a, amat32.p, ls, msc.p); break;
-    case 3: m2l_mfma32_kernel<3><<<g, 256, 0, s>>>(p, m2l_tiles.p, a, amat32.p, ls, msc.p); break;
-    case 4: m2l_mfma32_kernel<4><<<g, 256, 0, s>>>(p, m2l_tiles.p, a, amat32.p, ls, msc.p); break;
-    case 5: m2l_mfma32_kernel<5><<<g, 256, 0, s>>>(p, m2l_tiles.p, a, amat32.p, ls, msc.p); break;
-    case 6: m2l_mfma32_kernel<6><<<g, 256, 0, s>>>(p, m2l_tiles.p, a, amat32.p, ls, msc.p); break;
-    default: m2l_mfma32_kernel<7><<<g, 256, 0, s>>>(p, m2l_tiles.p, a, amat32.p, ls, msc.p); break;
+    case 1: m2l_mfma32_kernel<1><<<g, 256, 0, s>>>(p, m2l_tiles.p, a, amat32.p, ls, msc.p, stop); break;
+    case 2: m2l_mfma32_kernel<2><<<g, 256, 0, s>>>(p, m2l_tiles.p, a, amat32.p, ls, msc.p, stop); break;
+    case 3: m2l_mfma32_kernel<3><<<g, 256, 0, s>>>(p, m2l_tiles.p, a, amat32.p, ls, msc.p, stop); break;
+    case 4: m2l_mfma32_kernel<4><<<g, 256, 0, s>>>(p, m2l_tiles.p, a, amat32.p, ls, msc.p, stop); break;
+    case 5: m2l_mfma32_kernel<5><<<g, 256, 0, s>>>(p, m2l_tiles.p, a, amat32.p, ls, msc.p, stop); break;
+    case 6: m2l_mfma32_kernel<6><<<g, 256, 0, s>>>(p, m2l_tiles.p, a, amat32.p, ls, msc.p, stop); break;
+    default: m2l_mfma32_kernel<7><<<g, 256, 0, s>>>(p, m2l_tiles.p, a, amat32.p, ls, msc.p, stop); break;
   }
   YQ_HIP(hipGetLastError());
 }
@@ -1317,7 +1325,7 @@ void Fmm::tree_mfma(bool gather, int l, hipStream_t s) {
 
 // Multipole and local expansions of the leaves for density sigma (upward pass,
 // M2L, downward pass).
-void Fmm::expansions(const double* sigma, hipStream_t s, bool m2l32) {
+void Fmm::expansions(const double* sigma, hipStream_t s, bool m2l32, const int* stop) {
   YQ_REQUIRE(built, YQ_ESTATE, "FMM tree not built");
   const int K = 4 * p + 1;
   gather_kernel<<<(unsigned)((N + 255) / 256), 256, 0, s>>>(N, perm.p, sigma, wnxs.p, wnys.p, qx.p,
@@ -1325,7 +1333,7 @@ void Fmm::expansions(const double* sigma, hipStream_t s, bool m2l32) {
   FmmLevel& leaf = lv[depth];
   const int col = p <= kColMaxOrder;
   p2m_kernel<<<leaf.nbox, 64, col ? (size_t)(p + 2) * 64 * sizeof(double) : 0, s>>>(p, col, kappa, leaf_start.p, leaf_cnt.p, leaf.cx.p, leaf.cy.p, xs.p,
-                                      ys.p, qx.p, qy.p, leaf.M.p);
+                                      ys.p, qx.p, qy.p, leaf.M.p, stop);
   for (int l = depth - 1; l >= 2; --l) {
     if (use_mfma) {
       tree_mfma(true, l, s);
@@ -1337,9 +1345,9 @@ void Fmm::expansions(const double* sigma, hipStream_t s, bool m2l32) {
                                                             lv[l].M.p);
   }
   if (use_mfma && m2l32) {
-    m2l_mfma32(s);
+    m2l_mfma32(s, stop);
   } else if (use_mfma) {
-    m2l_mfma(s);
+    m2l_mfma(s, stop);
   } else {
     for (int l = 2; l <= depth; ++l) {
       const int64_t nt = (int64_t)lv[l].nbox * (p + 1);
@@ -1362,9 +1370,9 @@ void Fmm::expansions(const double* sigma, hipStream_t s, bool m2l32) {
 }
 
 void Fmm::apply(const double* sigma, double* partial, bool p2p_fp32, const double* tab,
-                hipStream_t s) {
+                hipStream_t s, const int* stop) {
   // the FP32-class (inner) operator also takes its M2L in FP32 when that is set up
-  expansions(sigma, s, p2p_fp32 && want_m2l32 && use_mfma);
+  expansions(sigma, s, p2p_fp32 && want_m2l32 && use_mfma, stop);
   FmmLevel& leaf = lv[depth];
   const int col = p <= kColMaxOrder;
   const size_t sh_l = (size_t)FB * (2 * sizeof(double2) + sizeof(float2)) +
@@ -1372,11 +1380,11 @@ void Fmm::apply(const double* sigma, double* partial, bool p2p_fp32, const doubl
   if (p2p_fp32)
     l2p_p2p_kernel<true><<<leaf.nbox, FB, sh_l, s>>>(p, kappa, 1, col, leaf_start.p, leaf_cnt.p, nbp.p,
                                                      nbi.p, leaf.cx.p, leaf.cy.p, leaf.L.p, xs.p, ys.p,
-                                                     qx.p, qy.p, perm.p, tab, partial);
+                                                     qx.p, qy.p, perm.p, tab, partial, stop);
   else
     l2p_p2p_kernel<false><<<leaf.nbox, FB, sh_l, s>>>(p, kappa, 1, col, leaf_start.p, leaf_cnt.p, nbp.p,
                                                       nbi.p, leaf.cx.p, leaf.cy.p, leaf.L.p, xs.p,
-                                                      ys.p, qx.p, qy.p, perm.p, tab, partial);
+                                                      ys.p, qx.p, qy.p, perm.p, tab, partial, stop);
   YQ_HIP(hipGetLastError());
 }
 

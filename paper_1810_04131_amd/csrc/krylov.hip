@@ -9,10 +9,12 @@ namespace yq {
 
 constexpr int KB = 256;
 
+// Row blocks of a multi-dot (the number of partials per column): at most 32, so
+// that one thread sums a column's partials with all of its loads in flight.
 int krylov_blocks(int64_t n) {
   int64_t nb = (n + 2047) / 2048;
   if (nb < 1) nb = 1;
-  if (nb > 1024) nb = 1024;
+  if (nb > 32) nb = 32;
   return (int)nb;
 }
 
@@ -23,6 +25,26 @@ __device__ __forceinline__ double block_sum_waves(double v, double* sh) {
   if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
   __syncthreads();
   return threadIdx.x == 0 ? ((sh[0] + sh[1]) + sh[2]) + sh[3] : 0.0;
+}
+
+// p[0] + p[1] + ... + p[nb - 1] in that order (nb <= 32 column partials: one
+// thread per column keeps every column in flight at once).  The update kernels,
+// the Arnoldi step and the host (sum_partials) use this order, so the same
+// partials give the same coefficient everywhere.
+__device__ __forceinline__ double sum_partials_dev(const double* __restrict__ p, int nb) {
+  double t = 0.0;
+  for (int b = 0; b < nb; ++b) t += p[b];
+  return t;
+}
+
+// p[0] + ... + p[nb - 1] by one wavefront (a long list: the |w|^2 partials of
+// the update blocks): each lane sums every 64th value in order, then a fixed
+// butterfly; every lane ends with the same value.
+__device__ __forceinline__ double wave_sum_partials(const double* __restrict__ p, int nb, int lane) {
+  double t = 0.0;
+  for (int b = lane; b < nb; b += 64) t += p[b];
+  for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+  return t;
 }
 
 // partial[k * nb + b] = sum over block b's rows of V[k][i] * w[i]; one block per
@@ -51,11 +73,7 @@ __global__ __launch_bounds__(KB) void update_partial_kernel(double* __restrict__
                                                             const double* __restrict__ partial,
                                                             int nb, double alpha, int64_t n) {
   extern __shared__ double h[];
-  for (int k = threadIdx.x; k < kc; k += KB) {
-    double t = 0.0;
-    for (int b = 0; b < nb; ++b) t += partial[(int64_t)k * nb + b];
-    h[k] = t;
-  }
+  for (int k = threadIdx.x; k < kc; k += KB) h[k] = sum_partials_dev(partial + (int64_t)k * nb, nb);
   __syncthreads();
   const int64_t i = blockIdx.x * (int64_t)KB + threadIdx.x;
   if (i >= n) return;
@@ -72,11 +90,7 @@ __global__ __launch_bounds__(KB) void update_norm_kernel(double* __restrict__ w,
                                                          int nb, double alpha, int64_t n,
                                                          double* __restrict__ npart) {
   extern __shared__ double h[];   // [kc] coefficients, then [KB / 64] wavefront sums
-  for (int k = threadIdx.x; k < kc; k += KB) {
-    double t = 0.0;
-    for (int b = 0; b < nb; ++b) t += partial[(int64_t)k * nb + b];
-    h[k] = t;
-  }
+  for (int k = threadIdx.x; k < kc; k += KB) h[k] = sum_partials_dev(partial + (int64_t)k * nb, nb);
   __syncthreads();
   const int64_t i = blockIdx.x * (int64_t)KB + threadIdx.x;
   double v = 0.0;
@@ -107,63 +121,7 @@ __global__ void axpby_kernel(double a, const double* __restrict__ x, double b,
   out[i] = a * x[i] + (y ? b * y[i] : 0.0);
 }
 
-// out = x * inv[0]
-__global__ void scale_kernel(const double* __restrict__ x, const double* __restrict__ inv,
-                             double* __restrict__ out, int64_t n) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  out[i] = x[i] * inv[0];
-}
-
 constexpr int MAXR = 200;   // largest restart length (checked with the parameters)
-
-__global__ __launch_bounds__(64) void arnoldi_kernel(const double* __restrict__ part, int nb, int j,
-                                                     int ldh, double* __restrict__ H,
-                                                     double* __restrict__ cs,
-                                                     double* __restrict__ sn,
-                                                     double* __restrict__ g,
-                                                     double* __restrict__ inv_hn,
-                                                     int* __restrict__ stop, double bnorm,
-                                                     double rtol, double* __restrict__ status) {
-  __shared__ double hc[MAXR + 2];
-  if (*stop) return;   // uniform: the cycle has already stopped
-  const int64_t pc = (int64_t)(j + 1) * nb;
-  for (int i = threadIdx.x; i <= j; i += 64) {
-    double a = 0.0, b = 0.0;
-    for (int q = 0; q < nb; ++q) a += part[(int64_t)i * nb + q];
-    for (int q = 0; q < nb; ++q) b += part[pc + (int64_t)i * nb + q];
-    hc[i] = a + b;
-  }
-  __syncthreads();
-  if (threadIdx.x != 0) return;
-  double h2 = 0.0;
-  for (int q = 0; q < nb; ++q) h2 += part[2 * pc + q];
-  const double hn = sqrt(fmax(h2, 0.0));
-  hc[j + 1] = hn;
-  for (int i = 0; i < j; ++i) {
-    const double t = cs[i] * hc[i] + sn[i] * hc[i + 1];
-    hc[i + 1] = -sn[i] * hc[i] + cs[i] * hc[i + 1];
-    hc[i] = t;
-  }
-  const double den = hypot(hc[j], hc[j + 1]);
-  const double c = den > 0.0 ? hc[j] / den : 1.0;
-  const double sv = den > 0.0 ? hc[j + 1] / den : 0.0;
-  cs[j] = c;
-  sn[j] = sv;
-  hc[j] = den;
-  hc[j + 1] = 0.0;
-  const double gj = g[j];
-  g[j + 1] = -sv * gj;
-  g[j] = c * gj;
-  const double rel = fabs(sv * gj) / bnorm;
-  for (int i = 0; i <= j + 1; ++i) H[(int64_t)j * ldh + i] = hc[i];
-  inv_hn[0] = hn > 0.0 ? 1.0 / hn : 0.0;
-  const int st = (rel <= rtol || hn == 0.0) ? 1 : 0;
-  *stop = st;
-  status[0] = rel;
-  status[1] = hn;
-  status[2] = (double)st;
-}
 
 // y = R^-1 g for the leading k x k upper triangle R of H (leading dimension
 // ldh), by back substitution: one wavefront, each row's dot product split over
@@ -204,20 +162,16 @@ __global__ __launch_bounds__(KB) void arnoldi_scale_kernel(
   if (threadIdx.x == 0) stopped = *stop;
   __syncthreads();
   if (stopped) return;   // uniform over the block
-  if (threadIdx.x < 64) {
-    double t = 0.0;
-    for (int q = threadIdx.x; q < nbu; q += 64) t += npart[q];
-    for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
-    if (threadIdx.x == 0) h2s = t;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (wave == 0) {
+    const double t = wave_sum_partials(npart, nbu, lane);
+    if (lane == 0) h2s = t;
   }
   if (blockIdx.x == 0) {
     const int64_t pc = (int64_t)(j + 1) * nb;
-    for (int i = threadIdx.x; i <= j; i += KB) {
-      double a = 0.0, b = 0.0;
-      for (int q = 0; q < nb; ++q) a += part[(int64_t)i * nb + q];
-      for (int q = 0; q < nb; ++q) b += part[pc + (int64_t)i * nb + q];
-      hc[i] = a + b;
-    }
+    for (int i = threadIdx.x; i <= j; i += KB)
+      hc[i] = sum_partials_dev(part + (int64_t)i * nb, nb) +
+              sum_partials_dev(part + pc + (int64_t)i * nb, nb);
   }
   __syncthreads();
   const double hn = sqrt(fmax(h2s, 0.0));
@@ -263,15 +217,6 @@ __global__ void gmres_init_kernel(double* __restrict__ g, int m, double beta,
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i <= m) g[i] = i == 0 ? beta : 0.0;
   if (i == 0) *stop = 0;
-}
-
-void launch_arnoldi(const double* part, int nb, int j, int ldh, double* H, double* cs, double* sn,
-                    double* g, double* inv_hn, int* stop, double bnorm, double rtol,
-                    double* status, hipStream_t s) {
-  YQ_REQUIRE(j >= 0 && j + 1 < ldh && j < MAXR, YQ_EINVAL, "arnoldi: column out of range");
-  arnoldi_kernel<<<1, 64, 0, s>>>(part, nb, j, ldh, H, cs, sn, g, inv_hn, stop, bnorm, rtol,
-                                  status);
-  YQ_HIP(hipGetLastError());
 }
 
 void launch_trisolve(const double* H, int ldh, const double* g, int k, double* y, hipStream_t s) {
@@ -342,9 +287,5 @@ void launch_axpby(double a, const double* x, double b, const double* y, double* 
   YQ_HIP(hipGetLastError());
 }
 
-void launch_scale(const double* x, const double* inv, double* out, int64_t n, hipStream_t s) {
-  scale_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(x, inv, out, n);
-  YQ_HIP(hipGetLastError());
-}
 
 }  // namespace yq

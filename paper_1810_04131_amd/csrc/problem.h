@@ -34,6 +34,7 @@ struct yq_problem {
   DevBuf<float4> fsrc;
   DevBuf<double> pot_partial;
   DevBuf<double> pfx, pfy, pfwx, pfwy, pfs;   // oversampled potential rule (PotFine)
+  DevBuf<double> qfx, qfy, qfwx, qfwy;         // oversampled points of the QBX build
   bool pot_fine_ready = false;                // pf* hold this geometry's points
   DevBuf<int> nb_ptr, nb_idx, bad, ncnt;
   DevBuf<int> xrow, xpan;

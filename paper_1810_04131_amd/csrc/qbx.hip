@@ -45,10 +45,16 @@ __device__ __forceinline__ void smooth_pair(const GeomView& g, double xi, double
   sgy = c * (k1z * qy - b * dy);
 }
 
+// The oversampled points of the window panels come from a per-geometry table
+// (fx, fy, and (fwx, fwy) = weight x unit normal, [panel * nsub * 16 + k]); the
+// normal and the weight enter the sums only through their product.
 template <int BS>
-__global__ __launch_bounds__(BS) void qbx_build_kernel(GeomView g, Consts c, int p, int win,
-                                                       int nsub, double radius,
-                                                       const double* __restrict__ L,
+__global__ __launch_bounds__(BS) void qbx_build_kernel(GeomView g, int p, int win, int nsub,
+                                                       double radius, const double* __restrict__ L,
+                                                       const double* __restrict__ fx,
+                                                       const double* __restrict__ fy,
+                                                       const double* __restrict__ fwx,
+                                                       const double* __restrict__ fwy,
                                                        double* __restrict__ W,
                                                        double* __restrict__ WGx,
                                                        double* __restrict__ WGy) {
@@ -87,7 +93,8 @@ __global__ __launch_bounds__(BS) void qbx_build_kernel(GeomView g, Consts c, int
 
   int kj = (k + slot - win) % P;
   if (kj < 0) kj += P;
-  const double* pp = g.pc + 5 * pid;
+  const int F = nsub * Q;
+  const int64_t fbase = ((int64_t)pid * P + kj) * F;
 
   double acc[Q], agx[Q], agy[Q];
 #pragma unroll
@@ -95,23 +102,9 @@ __global__ __launch_bounds__(BS) void qbx_build_kernel(GeomView g, Consts c, int
 
   for (int sub = 0; sub < nsub; ++sub) {
     for (int gq = 0; gq < Q; ++gq) {
-      const double xl = -1.0 + (2.0 * sub + c.xg[gq] + 1.0) / nsub;
-      const double t = 2.0 * PI / P * (kj + 0.5 * (xl + 1.0));
-      double yfx, yfy, nfx, nfy, sp;
-      {
-        double st, ct, sa, ca;
-        sincos(t, &st, &ct);
-        sincos(pp[2], &sa, &ca);
-        double ex = pp[3] * ct, ey = pp[4] * st;
-        double dx = -pp[3] * st, dy = pp[4] * ct;
-        yfx = pp[0] + ca * ex - sa * ey;
-        yfy = pp[1] + sa * ex + ca * ey;
-        double gx = ca * dx - sa * dy, gy = sa * dx + ca * dy;
-        sp = sqrt(gx * gx + gy * gy);
-        nfx = gy / sp;
-        nfy = -gx / sp;
-      }
-      const double wf = (PI / P / nsub) * c.wg[gq] * sp;
+      const int64_t fo = fbase + sub * Q + gq;
+      const double yfx = fx[fo], yfy = fy[fo];
+      const double nfx = fwx[fo], nfy = fwy[fo];   // weight x normal
 
       double cval = 0.0, gr = 0.0, gt = 0.0;
 #pragma unroll
@@ -163,7 +156,7 @@ __global__ __launch_bounds__(BS) void qbx_build_kernel(GeomView g, Consts c, int
         }
       }
       // rhat_x = -nu_i, thhat_x = (nu_iy, -nu_ix) for the exterior centre
-      const double w2 = wf / (2.0 * PI);
+      const double w2 = 1.0 / (2.0 * PI);
       const double cv = w2 * cval;
       const double gvx = w2 * (-gr * nxi + gt * nyi);
       const double gvy = w2 * (-gr * nyi - gt * nxi);
@@ -262,11 +255,13 @@ __global__ void near_rows_kernel(GeomView g, Consts c, int nsub, const double* _
   }
 }
 
-void launch_qbx_build(const GeomView& g, const Consts& c, int p, int win, int nsub, double radius,
-                      const double* L, double* W, double* WGx, double* WGy, hipStream_t s) {
+void launch_qbx_build(const GeomView& g, int p, int win, int nsub, double radius, const double* L,
+                      const double* fx, const double* fy, const double* fwx, const double* fwy,
+                      double* W, double* WGx, double* WGy, hipStream_t s) {
   constexpr int BS = 64;
   dim3 grid((unsigned)((g.N + BS - 1) / BS), (unsigned)(2 * win + 1));
-  qbx_build_kernel<BS><<<grid, BS, 0, s>>>(g, c, p, win, nsub, radius, L, W, WGx, WGy);
+  qbx_build_kernel<BS><<<grid, BS, 0, s>>>(g, p, win, nsub, radius, L, fx, fy, fwx, fwy, W, WGx,
+                                           WGy);
   YQ_HIP(hipGetLastError());
 }
 
