@@ -47,6 +47,7 @@ struct Fmm {
   DevBuf<float> amat32;   // scaled M2L matrices, the operand order of amat
   DevBuf<double> msc;     // s_n per level [level][n]
   PinnedBuf stage_up, stage_dn;   // set-up transfers (grow-only, reused by every build)
+  DevBuf<char> stage_dev;         // device side of the batched uploads and copies
   DevBuf<double> bbox;            // node bounding box (xmin, xmax, ymin, ymax)
   DevBuf<uint32_t> keys, skeys;   // finest-level Morton keys, unsorted / sorted
   DevBuf<int> iota;               // 0..N-1 (sort payload)

@@ -886,9 +886,33 @@ static inline void unmorton(int64_t k, int64_t& ix, int64_t& iy) {
 // Host-to-device uploads during set-up: each array is kept until finish(), which
 // packs them into the pinned staging buffer, issues one asynchronous copy per
 // array and waits for the stream.  Device buffers only grow (DevBuf::fit).
+// Many copies in one launch: block (item, slice) copies 32-bit words of item
+// blockIdx.x.  Every item's size is a multiple of 4 bytes (int, double, int2).
+struct CopyItem {
+  void* dst;
+  const void* src;
+  int64_t words;
+};
+
+constexpr int COPY_SLICES = 32;
+
+__global__ __launch_bounds__(256) void batch_copy_kernel(const CopyItem* __restrict__ items) {
+  const CopyItem it = items[blockIdx.x];
+  const uint32_t* __restrict__ src = static_cast<const uint32_t*>(it.src);
+  uint32_t* __restrict__ dst = static_cast<uint32_t*>(it.dst);
+  for (int64_t w = (int64_t)blockIdx.y * 256 + threadIdx.x; w < it.words;
+       w += (int64_t)COPY_SLICES * 256)
+    dst[w] = src[w];
+}
+
+// Collects host arrays for device buffers and sends them in one transfer: the
+// arrays and a table of (destination, staged source, size) go through pinned
+// memory in one host-to-device copy, and batch_copy_kernel moves each array to
+// its buffer.  (A copy call per array costs the host tens of microseconds each.)
 struct Uploader {
   hipStream_t s;
   PinnedBuf& stage;
+  DevBuf<char>& dstage;
   struct Item {
     void* dst;
     std::shared_ptr<void> keep;
@@ -896,29 +920,38 @@ struct Uploader {
     size_t bytes;
   };
   std::vector<Item> items;
-  Uploader(hipStream_t st, PinnedBuf& sb) : s(st), stage(sb) {}
+  Uploader(hipStream_t st, PinnedBuf& sb, DevBuf<char>& db) : s(st), stage(sb), dstage(db) {}
   Uploader(const Uploader&) = delete;
   Uploader& operator=(const Uploader&) = delete;
   template <class T>
   void operator()(DevBuf<T>& d, const std::vector<T>& h) {
+    static_assert(sizeof(T) % 4 == 0, "uploads move 32-bit words");
     d.fit(std::max<size_t>(h.size(), 1));
     if (h.empty()) return;
     auto c = std::make_shared<std::vector<T>>(h);
     items.push_back({d.p, c, c->data(), h.size() * sizeof(T)});
   }
   void finish() {
-    size_t total = 0;
-    for (const Item& it : items) total += (it.bytes + 255) & ~(size_t)255;
-    if (total) {
+    if (!items.empty()) {
+      size_t data = 0;
+      for (const Item& it : items) data += (it.bytes + 255) & ~(size_t)255;
+      const size_t total = data + items.size() * sizeof(CopyItem);
       stage.fit(total);
+      dstage.fit(total);
+      CopyItem* tab = reinterpret_cast<CopyItem*>(stage.p + data);
       size_t off = 0;
-      for (const Item& it : items) {
+      for (size_t k = 0; k < items.size(); ++k) {
+        const Item& it = items[k];
         std::memcpy(stage.p + off, it.src, it.bytes);
-        YQ_HIP(hipMemcpyAsync(it.dst, stage.p + off, it.bytes, hipMemcpyHostToDevice, s));
+        tab[k] = CopyItem{it.dst, dstage.p + off, (int64_t)(it.bytes / 4)};
         off += (it.bytes + 255) & ~(size_t)255;
       }
+      YQ_HIP(hipMemcpyAsync(dstage.p, stage.p, total, hipMemcpyHostToDevice, s));
+      batch_copy_kernel<<<dim3((unsigned)items.size(), COPY_SLICES), 256, 0, s>>>(
+          reinterpret_cast<const CopyItem*>(dstage.p + data));
+      YQ_HIP(hipGetLastError());
     }
-    YQ_HIP(hipStreamSynchronize(s));
+    YQ_HIP(hipStreamSynchronize(s));   // the pinned stage is reused by the next upload
     items.clear();
   }
 };
@@ -996,7 +1029,7 @@ void Fmm::build(int64_t n, double kap, int order, int lmax, const double* tab, h
   p = order;
   leaf_max = lmax;
   kappa = kap;
-  Uploader up(s, stage_up);
+  Uploader up(s, stage_up, stage_dev);
   YQ_HIP(hipEventSynchronize(dn_done));
   root_box(reinterpret_cast<const double*>(stage_dn.p), W, x0, y0);
   const uint32_t* skey = reinterpret_cast<const uint32_t*>(stage_dn.p + 4 * sizeof(double));
@@ -1172,7 +1205,7 @@ void Fmm::set_order(int q, const double* tab, hipStream_t s) {
                                                                         gmat.p);
     YQ_HIP(hipGetLastError());
     // 16-box tiles of every level with M2L terms, finest level first
-    Uploader up(s, stage_up);
+    Uploader up(s, stage_up, stage_dev);
     std::vector<int2> ht;
     for (int l = depth; l >= 2; --l)
       for (int b = 0; b < lv[l].nbox; b += 16) ht.push_back(make_int2(l, b));
@@ -1202,10 +1235,13 @@ void Fmm::set_order(int q, const double* tab, hipStream_t s) {
 
 // A second expansion order on the same tree: copies the tree (device to device).
 void Fmm::copy_tree(const Fmm& o, int q, const double* tab, hipStream_t s) {
+  // the device-to-device copies go in one batch_copy_kernel launch
+  std::vector<CopyItem> cp;
   auto dup = [&](auto& dst, const auto& src) {
     using T = std::remove_pointer_t<decltype(src.p)>;
+    static_assert(sizeof(T) % 4 == 0, "copies move 32-bit words");
     dst.fit(std::max<size_t>(src.n, 1));
-    if (src.n) YQ_HIP(hipMemcpyAsync(dst.p, src.p, src.n * sizeof(T), hipMemcpyDeviceToDevice, s));
+    if (src.n) cp.push_back(CopyItem{dst.p, src.p, (int64_t)(src.n * sizeof(T) / 4)});
   };
   depth = o.depth;
   leaf_max = o.leaf_max;
@@ -1241,6 +1277,17 @@ void Fmm::copy_tree(const Fmm& o, int q, const double* tab, hipStream_t s) {
   dup(leaf_cnt, o.leaf_cnt);
   dup(nbp, o.nbp);
   dup(nbi, o.nbi);
+  if (!cp.empty()) {
+    const size_t tb = cp.size() * sizeof(CopyItem);
+    stage_up.fit(tb);
+    stage_dev.fit(tb);
+    std::memcpy(stage_up.p, cp.data(), tb);
+    YQ_HIP(hipMemcpyAsync(stage_dev.p, stage_up.p, tb, hipMemcpyHostToDevice, s));
+    batch_copy_kernel<<<dim3((unsigned)cp.size(), COPY_SLICES), 256, 0, s>>>(
+        reinterpret_cast<const CopyItem*>(stage_dev.p));
+    YQ_HIP(hipGetLastError());
+    YQ_HIP(hipStreamSynchronize(s));   // before the stages are reused
+  }
   qx.fit(N);
   qy.fit(N);
   set_order(q, tab, s);
