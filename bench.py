@@ -47,13 +47,20 @@ sys.path.insert(0, ROOT)
 #         >= 2 and general: degree-20 Horner (40)                              = 113
 F32_CLASS = {"z8": 23, "z4": 25, "z2": 29, "general": 31}
 F64_CLASS = {"z8": 95, "z4": 103, "z2": 113, "general": 113}
+# VALU instructions per pair in the pair loops of far32_kernel / far64_kernel,
+# counted in their gfx950 assembly (hipcc -S of farfield.hip; the general path
+# executes both branches of K1(z)/z), and the chip's VALU issue rate: 256 CUs x
+# 4 SIMDs x 16 lanes x 2.4 GHz lane-instructions per second (FP32 and FP64 alike).
+F32_VALU = {"z8": 17, "z4": 18, "z2": 20, "general": 43}
+F64_VALU = {"z8": 65, "z4": 69, "z2": 73, "general": 194}
+VALU_ISSUE = 256 * 4 * 16 * 2.4e9
 
 
 def far_class_mix(x, y, kappa, panels=False):
     """Fraction of the N^2 far-field pairs in each kernel class, from the same
     bounding circles as the kernels (bounding-box centre, largest distance):
     per (64-target group, 256-source tile), and with panels=True (the FP32
-    kernel) per (group, 16-source panel) inside the tiles with close pairs."""
+    and FP64 far-field kernels) per (group, 16-source panel) inside the tiles with close pairs."""
     import numpy as np
     n = len(x)
 
@@ -572,7 +579,9 @@ def main():
     xn, yn = nd["x"].cpu().numpy(), nd["y"].cpu().numpy()
     mix = far_class_mix(xn, yn, args.kappa, panels=True)
     f32_pair = flops_per_pair(mix, F32_CLASS)
-    f64_pair = flops_per_pair(far_class_mix(xn, yn, args.kappa), F64_CLASS)
+    mix64 = mix   # the FP64 kernels split close tiles into panels the same way
+    f64_pair = flops_per_pair(mix64, F64_CLASS)
+    f64_valu = flops_per_pair(mix64, F64_VALU)
     achieved32 = f32_pair * pairs / avg32
     ms_step = t_all / args.steps * 1e3
 
@@ -631,10 +640,13 @@ def main():
                       "gmres_iterations": it64[-1] if it64 else None,
                       "far64_achieved_tflops": f64_pair * pairs / avg64b / 1e12 if n64b else None,
                       "far64_frac_of_fp64_peak": f64_pair * pairs / avg64b / PEAK_FP64 if n64b else None,
-                      "far64_flops_per_pair": f64_pair},
+                      "far64_flops_per_pair": f64_pair,
+                      "far64_valu_issue_frac": pairs / avg64b * f64_valu / VALU_ISSUE if n64b else None},
         "roofline": {"bound": "alu", "kernel": "far32_kernel", "achieved": achieved32 / 1e12,
                      "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s", "frac": achieved32 / PEAK_FP32,
                      "traffic": traffic_from_counters(pairs), "flops_per_pair": f32_pair,
+                     "valu_instr_per_pair": flops_per_pair(mix, F32_VALU),
+                     "valu_issue_frac": pairs / avg32 * flops_per_pair(mix, F32_VALU) / VALU_ISSUE,
                      "pair_classes": mix,
                      "source_sha256_16": source_hash(),
                      "pairs_per_launch": pairs, "avg_launch_ms": avg32 * 1e3},

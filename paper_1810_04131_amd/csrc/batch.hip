@@ -77,9 +77,17 @@ __global__ __launch_bounds__(BB) void bfar64_kernel(const ConfDev* __restrict__ 
       }
       __syncthreads();
       const int nb = (int)min((int64_t)BB, j1 - jb);
-      const int cls = live ? far64_class(cd.f32.grp, cd.f32.tile, grp, jb / FT, cd.kappa)
-                           : C64_GENERAL;
-      acc = far64_class_tile(cls, xi, yi, sxy, sq, nb, cd.kap2, tab, acc);
+      // a tile with close pairs is summed panel by panel, each with its own class
+      const int tcls = live ? far64_class(cd.f32.grp, cd.f32.tile, grp, jb / FT, cd.kappa)
+                            : C64_GENERAL;
+      for (int q = 0; q < nb;) {
+        const bool split = tcls == C64_GENERAL && live;
+        const int cls = split ? far64_class(cd.f32.grp, cd.f32.pan, grp, (jb + q) / Q, cd.kappa)
+                              : tcls;
+        const int len = split ? Q : nb - q;
+        acc = far64_class_tile(cls, xi, yi, sxy + q, sq + q, len, cd.kap2, tab, acc);
+        q += len;
+      }
     }
     if (i < N) cd.part64[(int64_t)w.z * N + i] = acc;
   }

@@ -150,6 +150,7 @@ struct GeomView {
   const double* tab;     // FP64 special-function coefficients (bessel.h, T_SIZE doubles)
   const double4* ftile;  // bounding circles of 256-node source tiles
   const double4* fgrp;   // bounding circles of 64-node target groups
+  const double4* fpan;   // bounding circles of 16-node panels
 };
 
 // Discretisation constants, passed to kernels by value.

@@ -68,8 +68,15 @@ __global__ __launch_bounds__(FAR_BS) void far64_kernel(GeomView g, const double*
     }
     __syncthreads();
     const int nb = (int)min((int64_t)FAR_BS, j1 - jb);
-    const int cls = live ? far64_class(g.fgrp, g.ftile, grp, jb / FT, g.kappa) : C64_GENERAL;
-    acc = far64_class_tile(cls, xi, yi, sxy, sq, nb, kap2, g.tab, acc);
+    // a tile with close pairs is summed panel by panel, each with its own class
+    const int tcls = live ? far64_class(g.fgrp, g.ftile, grp, jb / FT, g.kappa) : C64_GENERAL;
+    for (int q = 0; q < nb;) {
+      const bool split = tcls == C64_GENERAL && live;
+      const int cls = split ? far64_class(g.fgrp, g.fpan, grp, (jb + q) / Q, g.kappa) : tcls;
+      const int len = split ? Q : nb - q;
+      acc = far64_class_tile(cls, xi, yi, sxy + q, sq + q, len, kap2, g.tab, acc);
+      q += len;
+    }
   }
   if (i < N) partial[(int64_t)blockIdx.y * N + i] = acc;
 }
@@ -166,8 +173,14 @@ __global__ __launch_bounds__(FAR_BS) void far_grad64_kernel(GeomView g,
     }
     __syncthreads();
     const int nb = (int)min((int64_t)FAR_BS, j1 - jb);
-    const int cls = live ? far64_class(g.fgrp, g.ftile, grp, jb / FT, g.kappa) : C64_GENERAL;
-    far_grad64_class_tile(cls, xi, yi, sxy, sq, nb, kap2, g.tab, ax, ay);
+    const int tcls = live ? far64_class(g.fgrp, g.ftile, grp, jb / FT, g.kappa) : C64_GENERAL;
+    for (int q = 0; q < nb;) {   // as in far64_kernel
+      const bool split = tcls == C64_GENERAL && live;
+      const int cls = split ? far64_class(g.fgrp, g.fpan, grp, (jb + q) / Q, g.kappa) : tcls;
+      const int len = split ? Q : nb - q;
+      far_grad64_class_tile(cls, xi, yi, sxy + q, sq + q, len, kap2, g.tab, ax, ay);
+      q += len;
+    }
   }
   if (i < N) {
     partial[((int64_t)blockIdx.y * 2 + 0) * N + i] = ax;
@@ -205,8 +218,14 @@ __global__ __launch_bounds__(FAR_BS) void far_fused64_kernel(GeomView g,
     }
     __syncthreads();
     const int nb = (int)min((int64_t)FAR_BS, j1 - jb);
-    const int cls = live ? far64_class(g.fgrp, g.ftile, grp, jb / FT, g.kappa) : C64_GENERAL;
-    far_fused64_class_tile(cls, xi, yi, sxy, sq, nb, kap2, g.tab, acc, ax, ay);
+    const int tcls = live ? far64_class(g.fgrp, g.ftile, grp, jb / FT, g.kappa) : C64_GENERAL;
+    for (int q = 0; q < nb;) {   // as in far64_kernel
+      const bool split = tcls == C64_GENERAL && live;
+      const int cls = split ? far64_class(g.fgrp, g.fpan, grp, (jb + q) / Q, g.kappa) : tcls;
+      const int len = split ? Q : nb - q;
+      far_fused64_class_tile(cls, xi, yi, sxy + q, sq + q, len, kap2, g.tab, acc, ax, ay);
+      q += len;
+    }
   }
   if (i < N) {
     partial[(int64_t)blockIdx.y * N + i] = acc;

@@ -132,6 +132,7 @@ struct yq_problem {
     g.tab = tab.p;
     g.ftile = ftile.p;
     g.fgrp = fgrp.p;
+    g.fpan = fpan.p;
     return g;
   }
 };
