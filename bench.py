@@ -154,9 +154,9 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_from_counters(launch_pairs):
-    """HBM bytes per far32 launch from the committed counter summary, or None when
-    the kernel source has changed since the counters were taken."""
+def counters(key):
+    """A per-launch figure from the committed counter summary, or None when the
+    far-field source has changed since the counters were taken."""
     path = os.path.join(ROOT, COUNTERS_FILE)
     if not os.path.exists(path):
         return None
@@ -168,9 +168,14 @@ def traffic_from_counters(launch_pairs):
     if kv.get("source_sha256_16") != source_hash():
         return None
     try:
-        return float(kv["hbm_bytes_per_launch"])
+        return float(kv[key])
     except (KeyError, ValueError):
         return None
+
+
+def traffic_from_counters(launch_pairs):
+    """HBM bytes per far32 launch (FETCH_SIZE + WRITE_SIZE, calibrated)."""
+    return counters("hbm_bytes_per_launch")
 
 
 def copy_probe():
@@ -704,12 +709,20 @@ def main():
                       "far64_achieved_tflops": f64_pair * pairs / avg64b / 1e12 if n64b else None,
                       "far64_frac_of_fp64_peak": f64_pair * pairs / avg64b / PEAK_FP64 if n64b else None,
                       "far64_flops_per_pair": f64_pair,
-                      "far64_valu_issue_frac": pairs / avg64b * f64_valu / VALU_ISSUE if n64b else None},
+                      "far64_valu_issue_frac": pairs / avg64b * f64_valu / VALU_ISSUE if n64b else None,
+                      "far64_counter_frac": (counters("far64_valu_flops_per_launch") / avg64b / PEAK_FP64
+                                             if n64b and counters("far64_valu_flops_per_launch")
+                                             else None)},
         "roofline": {"bound": "alu", "kernel": "far32_kernel", "achieved": achieved32 / 1e12,
                      "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s", "frac": achieved32 / PEAK_FP32,
                      "traffic": traffic_from_counters(pairs), "flops_per_pair": f32_pair,
                      "valu_instr_per_pair": flops_per_pair(mix, F32_VALU),
                      "valu_issue_frac": pairs / avg32 * flops_per_pair(mix, F32_VALU) / VALU_ISSUE,
+                     # the same launch's flops from the VALU instruction counters
+                     # (64 x (ADD + MUL + 2 FMA + TRANS) FP32 wave instructions)
+                     "counter_flops_per_launch": counters("far32_valu_flops_per_launch"),
+                     "counter_frac": (counters("far32_valu_flops_per_launch") / avg32 / PEAK_FP32
+                                      if counters("far32_valu_flops_per_launch") else None),
                      "pair_classes": mix,
                      "source_sha256_16": source_hash(),
                      "pairs_per_launch": pairs, "avg_launch_ms": avg32 * 1e3},
