@@ -124,6 +124,50 @@ def test_fmm_inner_solve_reaches_direct_tolerance(resid_order):
     assert _rel(_np(sig), so) < 1e-8
 
 
+@pytest.mark.parametrize("resid_order", [0, 40])
+def test_fmm_solve_forces_matches_solve_then_forces(resid_order):
+    """With the FMM the solve's residuals are not fused with the gradient: the
+    forces come from the FMM (or direct) gradient pass, as after a separate solve."""
+    torch = _torch()
+    parts = workloads.random_ellipses(6, 12.0, 1.1, seed=7)
+    prm = dict(panels_per_particle=16, qbx_order=8, far_mode=yq.YQ_FAR_FMM, fmm_order=16,
+               fmm_leaf_max=32, precision=yq.YQ_MIXED, tol=1e-9, fmm_resid_order=resid_order)
+    pa = yq.Problem(yq.default_params(**prm))
+    pa.set_workload(parts)
+    pa.set_boundary_data(pa.boundary_label())
+    sa, ia = pa.solve()
+    Fa, Ta, Ea = pa.forces(sa, gamma=0.7)
+    pf = yq.Problem(yq.default_params(**prm))
+    pf.set_workload(parts)
+    pf.set_boundary_data(pf.boundary_label())
+    sf, inf_, Ff, Tf, Ef = pf.solve_forces(gamma=0.7)
+    assert inf_["iterations"] == ia["iterations"] and inf_["residual"] <= 1e-9
+    assert _rel(_np(sf), _np(sa)) < 1e-13
+    assert _rel(_np(Ff), _np(Fa)) < 1e-12 and _rel(_np(Tf), _np(Ta)) < 1e-12
+    assert abs(Ef - Ea) <= 1e-12 * abs(Ea)
+
+
+def test_solve_forces_at_the_iteration_limit():
+    """ENOCONV from yq_solve_forces: sigma is the last iterate and the forces are
+    those of it (the direct path, where the last residual may be fused)."""
+    torch = _torch()
+    parts = workloads.random_ellipses(6, 12.0, 1.1, seed=7)
+    prm = dict(panels_per_particle=16, qbx_order=8, precision=yq.YQ_MIXED, tol=1e-12, maxiter=5)
+    pf = yq.Problem(yq.default_params(**prm))
+    pf.set_workload(parts)
+    pf.set_boundary_data(pf.boundary_label())
+    sf, inf_, Ff, Tf, Ef = pf.solve_forces(gamma=1.0, allow_noconv=True)
+    assert inf_["iterations"] == 5 and inf_["residual"] > 1e-12
+    pa = yq.Problem(yq.default_params(**prm))
+    pa.set_workload(parts)
+    pa.set_boundary_data(pa.boundary_label())
+    Fa, Ta, Ea = pa.forces(sf, gamma=1.0)
+    assert _rel(_np(Ff), _np(Fa)) < 1e-12 and _rel(_np(Tf), _np(Ta)) < 1e-12
+    assert abs(Ef - Ea) <= 1e-12 * abs(Ea)
+    with pytest.raises(yq.YQError):
+        pf.solve_forces()
+
+
 def test_fmm_large_workload_residual_property():
     _torch()
     cfg = workloads.config_large(seed=0)
