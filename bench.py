@@ -51,7 +51,7 @@ F64_CLASS = {"z8": 95, "z4": 103, "z2": 113, "general": 113}
 # counted in their gfx950 assembly (hipcc -S of farfield.hip; the general path
 # executes both branches of K1(z)/z), and the chip's VALU issue rate: 256 CUs x
 # 4 SIMDs x 16 lanes x 2.4 GHz lane-instructions per second (FP32 and FP64 alike).
-F32_VALU = {"z8": 17, "z4": 18, "z2": 20, "general": 43}
+F32_VALU = {"z8": 16, "z4": 17, "z2": 19, "general": 43}
 F64_VALU = {"z8": 65, "z4": 69, "z2": 73, "general": 194}
 VALU_ISSUE = 256 * 4 * 16 * 2.4e9
 

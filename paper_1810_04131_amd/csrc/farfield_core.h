@@ -90,18 +90,19 @@ __device__ __forceinline__ float far32_tile(double xi, double yi, const double2*
 
 
 // Far pairs: with D = s (x_i - y_j), Z2 = |D|^2 = (z log2 e)^2, Y = 1/sqrt(Z2),
-// K1(z)/z ((x_i - y_j) . q) = 2^-Z h1(2 log2(e) Y) (Y / sqrt(Z)) (D . q').  H is
-// the fit of h1 for the tile's range of z (z >= 2, 4 or 8), as a polynomial in Y.
+// K1(z)/z ((x_i - y_j) . q) = 2^-Z Z^-3/2 h1(2 log2(e) Y) (D . q').  H is the fit
+// of h1 for the tile's range of z (z >= 2, 4 or 8), as a polynomial in Y.  The
+// factor 2^-Z Z^-3/2 is one exp2 of -(Z + 1.5 log2 Z): its rounding adds little to
+// that of -Z itself, which already sets the factor's relative error.
 template <int NH, const float (&H)[NH]>
 __device__ __forceinline__ float far32_pair(float tx, float ty, float4 p, float acc) {
   const float dx = tx - p.x, dy = ty - p.y;
   const float z2 = fmaf(dx, dx, dy * dy);
   const float yv = __builtin_amdgcn_rsqf(z2);
   const float z = z2 * yv;
-  const float e = __builtin_amdgcn_exp2f(-z);
-  const float q = __builtin_amdgcn_rsqf(z);
+  const float e = __builtin_amdgcn_exp2f(fmaf(-1.5f, __builtin_amdgcn_logf(z), -z));
   const float h = horner(H, yv);
-  return fmaf((e * h) * (q * yv), fmaf(dx, p.z, dy * p.w), acc);
+  return fmaf(e * h, fmaf(dx, p.z, dy * p.w), acc);
 }
 
 __device__ __forceinline__ float4 ld_rec(kptr<float> p) {

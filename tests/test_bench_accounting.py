@@ -46,5 +46,5 @@ def test_class_mix_of_separated_clusters():
 def test_weighted_counts():
     mix = {"z8": 0.5, "z4": 0.25, "z2": 0.125, "general": 0.125}
     assert bench.flops_per_pair(mix, bench.F32_CLASS) == 0.5 * 23 + 0.25 * 25 + 0.125 * 29 + 0.125 * 31
-    assert bench.flops_per_pair(mix, bench.F32_VALU) == 0.5 * 17 + 0.25 * 18 + 0.125 * 20 + 0.125 * 43
+    assert bench.flops_per_pair(mix, bench.F32_VALU) == 0.5 * 16 + 0.25 * 17 + 0.125 * 19 + 0.125 * 43
     assert bench.VALU_ISSUE == 256 * 4 * 16 * 2.4e9
