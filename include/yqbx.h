@@ -116,8 +116,8 @@ const char* yq_last_error(const yq_problem* prob);
 /* All later work of the problem is issued on this HIP stream (hipStream_t; NULL = default). */
 int yq_set_stream(yq_problem* prob, void* hip_stream);
 
-/* Geometry and set-up (steps a1 geometry, a3 QBX centres and near lists,
- * a4 QBX correction build; section 2.1 particles, section 5 discretisation).
+/* Geometry and set-up (geometry, QBX centres and near lists, QBX correction
+ * build; section 2.1 particles, section 5 discretisation).
  * center_xy: host [2n] (x0,y0,x1,y1,...); angle: host [n] director angles;
  * semi_axes: host [2n] (A0,B0,A1,B1,...), A >= B > 0; kappa > 0.
  * Builds nodes, normals, weights, near lists and the FP64 QBX correction of
@@ -131,17 +131,17 @@ int yq_set_particles(yq_problem* prob, int32_t n, const double* center_xy, const
 int yq_num_nodes(const yq_problem* prob, int64_t* N);
 int yq_num_particles(const yq_problem* prob, int32_t* n);
 
-/* Node data (step a1): dev x,y,nx,ny,w each [N] (any may be NULL).  Synchronous. */
+/* Node data (section 5 discretisation): dev x,y,nx,ny,w each [N] (any may be NULL).  Synchronous. */
 int yq_get_nodes(const yq_problem* prob, double* x, double* y, double* nx, double* ny, double* w);
 
-/* Extra near panels (step a3): panels outside a target's QBX window whose
+/* Extra near panels (section 5): panels outside a target's QBX window whose
  * nearest node is closer than near_beta * h.  yq_near_count gives their total;
  * yq_get_near fills dev row_ptr [N+1] and dev panels [total] (global panel
  * index = particle * P + k), rows in node order, panels ascending. */
 int yq_near_count(const yq_problem* prob, int64_t* total);
 int yq_get_near(const yq_problem* prob, int32_t* row_ptr, int32_t* panels);
 
-/* Boundary labels (step a2): writes dev f [N].  YQ_LABEL_ARC: smoothed arc
+/* Boundary labels (eq. JanusBC): writes dev f [N].  YQ_LABEL_ARC: smoothed arc
  * f = 1/2 [tanh((phi+a)/b) - tanh((phi-a)/b)], a = param0 (half opening),
  * b = param1 (edge width), phi in (-pi, pi] the polar angle from the director.
  * YQ_LABEL_JANUS: f = 1 - sin^p(phi/2), p = param0 (eq. JanusBC, read with
@@ -151,9 +151,9 @@ int yq_boundary_label(yq_problem* prob, int32_t kind, double param0, double para
 /* Sets the Dirichlet data f (dev [N], copied). */
 int yq_set_boundary_data(yq_problem* prob, const double* f);
 
-/* Far field alone (step a5): out_i = sum_{j != i} w_j dG/dnu_y(x_i, y_j) sigma_j
+/* Far field alone (the Nystrom rule of eq. double-layer-def): out_i = sum_{j != i} w_j dG/dnu_y(x_i, y_j) sigma_j
  * over every node pair, in FP64 (YQ_FP64) or FP32 arithmetic (YQ_MIXED).  With
- * the FMM enabled (far_mode) YQ_MIXED gives the FMM far field (step a7: FP64
+ * the FMM enabled (far_mode) YQ_MIXED gives the FMM far field (FP64
  * expansions, FP32 leaf-neighbour interactions) and YQ_FMM64 the FMM with FP64
  * leaf-neighbour interactions.  dev sigma [N], dev out [N].  Asynchronous.
  *
@@ -164,34 +164,34 @@ int yq_set_boundary_data(yq_problem* prob, const double* f);
  * it is 0); yq_apply_operator(YQ_FP64) is always the exact direct sum. */
 int yq_apply_far(yq_problem* prob, const double* sigma, double* out, int32_t precision);
 
-/* The discrete operator (steps a5 + a6): out = (1/2 I + D) sigma with the
+/* The discrete operator (far field + QBX near correction): out = (1/2 I + D) sigma with the
  * QBX near correction (eq. bie).  dev sigma [N], dev out [N] (must not alias).
  * Asynchronous on the problem's stream. */
 int yq_apply_operator(yq_problem* prob, const double* sigma, double* out, int32_t precision);
 
-/* GMRES solve of eq. bie for the data set by yq_set_boundary_data (steps a8,
- * a9).  dev sigma0 [N] initial guess or NULL (zero); dev sigma [N] result;
+/* GMRES solve of eq. bie for the data set by yq_set_boundary_data (section 5).
+ * dev sigma0 [N] initial guess or NULL (zero); dev sigma [N] result;
  * info: host, may be NULL.  Synchronous.  YQ_ENOCONV: not converged (sigma
  * holds the last iterate). */
 int yq_solve(yq_problem* prob, const double* sigma0, double* sigma, yq_solve_info* info);
 
-/* Exterior-limit surface gradient of u = D[sigma] at the nodes (step a10):
- * dev gx, gy [N].  The far part is the direct FP64 sum, or with the FMM
+/* Exterior-limit surface gradient of u = D[sigma] at the nodes (eq. intrep
+ * differentiated): dev gx, gy [N].  The far part is the direct FP64 sum, or with the FMM
  * enabled the FP64 FMM gradient (order fmm_resid_order, else fmm_order): the
  * local expansions' gradient plus direct neighbour-leaf interactions.
  * Asynchronous. */
 int yq_surface_gradient(yq_problem* prob, const double* sigma, double* gx, double* gy);
 
-/* Hydrophobic forces and torques (step a11, eqs. stress, force_torque,
+/* Hydrophobic forces and torques (eqs. stress, force_torque,
  * scalar-torque): u = f on Sigma, grad u from yq_surface_gradient.
  * dev force [2n] (Fx0,Fy0,...), dev torque [n] about each centre a_i,
  * host energy (may be NULL): Phi = -gamma/kappa int f du/dnu ds.  Synchronous. */
 int yq_forces(yq_problem* prob, const double* sigma, double gamma, double* force, double* torque,
               double* energy);
 
-/* Algorithm 1 end to end: yq_solve, then yq_forces of its sigma (steps a9 +
- * a11), with the same arguments and results as those two calls.  With the
- * direct far field, a YQ_MIXED solve computes the FP64 residual it expects to
+/* The solve-and-forces part of a time step of Algorithm 1: yq_solve, then
+ * yq_forces of its sigma (eqs. bie, stress, force_torque), with the same
+ * arguments and results as those two calls.  With the direct far field, a YQ_MIXED solve computes the FP64 residual it expects to
  * be its last one together with the gradient far field of the same sigma (one
  * pass over the node pairs instead of two); the forces then reuse it.  If that
  * residual was not the last, the gradient is computed afresh.  Results agree
@@ -200,13 +200,13 @@ int yq_forces(yq_problem* prob, const double* sigma, double gamma, double* force
 int yq_solve_forces(yq_problem* prob, const double* sigma0, double* sigma, yq_solve_info* info,
                     double gamma, double* force, double* torque, double* energy);
 
-/* Off-surface potential u = D[sigma] (step a12, eq. intrep) at M targets:
+/* Off-surface potential u = D[sigma] (eq. intrep) at M targets:
  * dev tx, ty [M], dev u [M].  Panels whose nearest node is closer than
  * pot_beta*h use a pot_oversample-fold oversampled rule.  Asynchronous. */
 int yq_eval_potential(yq_problem* prob, const double* sigma, int64_t M, const double* tx,
                       const double* ty, double* u);
 
-/* ---- Batched solves (step a13) --------------------------------------------------------
+/* ---- Batched solves -------------------------------------------------------------------
  * A batch holds many independent configurations.  Their nodes are laid out one
  * after another (configuration c at offset offsets[c] of every batch vector, in
  * the node order of a single problem) and every GMRES iteration of the whole
@@ -269,7 +269,7 @@ int yq_batch_autotune(yq_batch* batch, int32_t* persist_blocks, int32_t* far_wan
 /* enable != 0: replay the captured iteration graph (default); 0: launch eagerly. */
 int yq_batch_use_graphs(yq_batch* batch, int32_t enable);
 
-/* ---- Serving (step a14) ------------------------------------------------------------------
+/* ---- Serving -----------------------------------------------------------------------------
  * A continuous-batching solve server on one GPU.  Requests (one particle
  * configuration each) are queued by yq_server_submit and advanced by
  * yq_server_step, one scheduling tick per call:

@@ -1,4 +1,4 @@
-// Step a13: many independent configurations solved together.
+// Many independent configurations solved together.
 //
 // Each configuration is an ordinary problem (geometry, near lists and QBX
 // correction built by yq_set_particles).  Its node range lives at a fixed

@@ -1,4 +1,4 @@
-// Steps a5 (tiled direct far field) and a6 (near-correction apply).
+// The tiled direct far field and the near-correction apply.
 //
 // Far field: out_i = (kappa^2/2pi) sum_{j != i} [K1(z)/z] ((x_i - y_j) . q_j),
 // z = kappa |x_i - y_j|, q_j = w_j sigma_j nu_j -- the 16-point Nystrom rule of

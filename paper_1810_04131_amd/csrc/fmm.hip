@@ -1,4 +1,4 @@
-// Step a7: quadtree Yukawa FMM for the double-layer far field.
+// Quadtree Yukawa FMM for the double-layer far field.
 //
 // Expansions follow Graf's addition theorem for the modified Bessel functions
 // (the Yukawa case of section 5's eq. graf-addition).  With

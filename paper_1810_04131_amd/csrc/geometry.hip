@@ -1,4 +1,4 @@
-// Step a1 (nodes, normals, weights), a2 (boundary labels) and a3 (near lists,
+// Nodes, normals and weights, boundary labels, and near lists (with the
 // geometry check) of the solve.  Particles are the ellipses of section 2.1;
 // panels are the composite Gauss-Legendre panels of section 5.
 #include <cmath>

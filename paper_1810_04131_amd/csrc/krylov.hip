@@ -1,4 +1,4 @@
-// Step a8: vector kernels for GMRES (Algorithm 1 solves eq. bie with GMRES).
+// Vector kernels for GMRES (Algorithm 1 solves eq. bie with GMRES).
 // Arnoldi uses classical Gram-Schmidt applied twice, so each orthogonalisation
 // is two multi-dot products and two updates.  Dot products reduce in a fixed
 // order (per-block partials, then one block per column), so results do not

@@ -1,4 +1,4 @@
-// Steps a11 (stress, forces, torques, energy), a12 (off-surface potential)
+// Stress, forces, torques and energy; the off-surface potential;
 // and the special-function test entry.
 //
 // Stress (eq. stress) with rho = 1/kappa and nu the unit normal into the water:

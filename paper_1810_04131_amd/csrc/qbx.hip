@@ -1,4 +1,4 @@
-// Step a4: the FP64 QBX near correction of the operator and of its surface gradient.
+// The FP64 QBX near correction of the operator and of its surface gradient.
 //
 // For target x_i on panel k the contribution of the window panels k-win..k+win
 // goes through local expansions about c = x_i +/- r nu_i, r = radius * h_k

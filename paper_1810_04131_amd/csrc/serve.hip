@@ -1,4 +1,4 @@
-// Step a14: a continuous-batching solve server.
+// A continuous-batching solve server.
 //
 // Requests (particle configurations of any size) are queued on submit.  Each
 // call to step() is one scheduling tick:

@@ -5,7 +5,7 @@ Tolerances (relative to the largest magnitude of the compared quantity):
   of ~N terms, FP64 special functions within 1e-15);  FP32 far field 5e-6 (FP32
   unit roundoff 6e-8 in each term, special functions within 3e-7, summed over up
   to N terms of mixed sign);
-  FP64 solve 1e-10 (the benchmark spec's bound; GMRES run to 1e-13 so the discrete
+  FP64 solve 1e-10 (the FP64 path's target bound; GMRES run to 1e-13 so the discrete
   solution's rounding dominates);  mixed solve 1e-8.
 """
 import dataclasses
