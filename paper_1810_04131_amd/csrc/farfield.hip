@@ -101,26 +101,39 @@ __global__ __launch_bounds__(FAR_BS) void far32_kernel(Far32View v, int chunk,
 // Bounding circle of nodes [g G, min(N, g G + G)): centre of the bounding box,
 // radius = largest distance from it, enlarged by a relative 1e-12 so that
 // rounding cannot leave a node outside.
-__global__ void circles_kernel(const double* __restrict__ x, const double* __restrict__ y,
-                               int64_t N, int G, int64_t ng, double4* __restrict__ out) {
-  const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (g >= ng) return;
+// One wavefront per circle (four per block): lanes take every 64th node, and
+// the bounds and the largest distance are wave reductions (min and max do not
+// depend on the order, so the circle is the same as from a serial pass).
+__global__ __launch_bounds__(256) void circles_kernel(const double* __restrict__ x,
+                                                      const double* __restrict__ y, int64_t N,
+                                                      int G, int64_t ng,
+                                                      double4* __restrict__ out) {
+  const int64_t g = blockIdx.x * (int64_t)4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (g >= ng) return;   // uniform over the wavefront
   const int64_t a = g * G, b = min(N, a + G);
-  double x0 = x[a], x1 = x0, y0 = y[a], y1 = y0;
-  for (int64_t j = a + 1; j < b; ++j) {
+  double x0 = INFINITY, x1 = -INFINITY, y0 = INFINITY, y1 = -INFINITY;
+  for (int64_t j = a + lane; j < b; j += 64) {
     x0 = fmin(x0, x[j]);
     x1 = fmax(x1, x[j]);
     y0 = fmin(y0, y[j]);
     y1 = fmax(y1, y[j]);
   }
+  for (int o = 32; o > 0; o >>= 1) {
+    x0 = fmin(x0, __shfl_xor(x0, o, 64));
+    x1 = fmax(x1, __shfl_xor(x1, o, 64));
+    y0 = fmin(y0, __shfl_xor(y0, o, 64));
+    y1 = fmax(y1, __shfl_xor(y1, o, 64));
+  }
   const double cx = 0.5 * (x0 + x1), cy = 0.5 * (y0 + y1);
   double r2 = 0.0;
-  for (int64_t j = a; j < b; ++j) {
+  for (int64_t j = a + lane; j < b; j += 64) {
     const double dx = x[j] - cx, dy = y[j] - cy;
     r2 = fmax(r2, dx * dx + dy * dy);
   }
+  for (int o = 32; o > 0; o >>= 1) r2 = fmax(r2, __shfl_xor(r2, o, 64));
   const double r = sqrt(r2);
-  out[g] = make_double4(cx, cy, r + 1e-12 * (r + fabs(cx) + fabs(cy)), 0.0);
+  if (lane == 0) out[g] = make_double4(cx, cy, r + 1e-12 * (r + fabs(cx) + fabs(cy)), 0.0);
 }
 
 // Node positions relative to their tile centre, scaled by s = kappa log2(e).
@@ -235,10 +248,10 @@ __global__ __launch_bounds__(FAR_BS) void far_fused64_kernel(GeomView g,
 }
 
 // out_i = (kappa^2/2pi) sum_chunks partial + sum_window W sigma + sum_extra vals sigma.
-// Four lanes per node (a quad of one wavefront): lane q sums chunks q, q + 4, ...
-// and the terms m = 4q .. 4q + 3 of every window panel and extra panel; the quad
-// then combines its sums in a fixed order.  A node's quad is either wholly
-// inside [0, N) or wholly past it.
+// Eight lanes per node (an aligned group of one wavefront): lane q sums chunks
+// q, q + 8, ... and the terms m = 2q, 2q + 1 of every window panel and extra
+// panel; the group then combines its sums in a fixed order.  A node's group is
+// either wholly inside [0, N) or wholly past it.
 __global__ __launch_bounds__(256) void finish_kernel(GeomView g, int win, int chunks,
                                                      const double* __restrict__ p64,
                                                      const float* __restrict__ p32,
@@ -250,14 +263,14 @@ __global__ __launch_bounds__(256) void finish_kernel(GeomView g, int win, int ch
                                                      double* __restrict__ out) {
   const int64_t N = g.N;
   const int64_t t = blockIdx.x * (int64_t)256 + threadIdx.x;
-  const int64_t i = t >> 2;
-  const int q = (int)(t & 3);
+  const int64_t i = t >> 3;
+  const int q = (int)(t & 7);
   if (i >= N) return;
   double s = 0.0;
   if (p64) {
-    for (int c = q; c < chunks; c += 4) s += p64[(int64_t)c * N + i];
+    for (int c = q; c < chunks; c += 8) s += p64[(int64_t)c * N + i];
   } else {
-    for (int c = q; c < chunks; c += 4) s += (double)p32[(int64_t)c * N + i];
+    for (int c = q; c < chunks; c += 8) s += (double)p32[(int64_t)c * N + i];
   }
   double corr = 0.0;
   if (win >= 0) {
@@ -265,27 +278,27 @@ __global__ __launch_bounds__(256) void finish_kernel(GeomView g, int win, int ch
     const int64_t pan = i / Q;
     const int64_t pid = pan / P;
     const int k = (int)(pan % P);
-    const int m0 = 4 * q;
+    const int m0 = 2 * q;
     for (int sl = 0; sl <= 2 * win; ++sl) {
       int kj = (k + sl - win) % P;
       if (kj < 0) kj += P;
       const double* sg = sigma + (pid * P + kj) * Q + m0;
       const double* wr = W + ((int64_t)sl * Q + m0) * N + i;
-#pragma unroll
-      for (int mm = 0; mm < 4; ++mm) corr = fma(wr[(int64_t)mm * N], sg[mm], corr);
+      corr = fma(wr[0], sg[0], corr);
+      corr = fma(wr[N], sg[1], corr);
     }
     if (xvals)
       for (int e = xrow[i]; e < xrow[i + 1]; ++e) {
         const double* sg = sigma + (int64_t)xpan[e] * Q + m0;
         const double* vr = xvals + (int64_t)e * Q + m0;
-#pragma unroll
-        for (int mm = 0; mm < 4; ++mm) corr = fma(vr[mm], sg[mm], corr);
+        corr = fma(vr[0], sg[0], corr);
+        corr = fma(vr[1], sg[1], corr);
       }
   }
-  s += __shfl_xor(s, 1, 64);
-  s += __shfl_xor(s, 2, 64);
-  corr += __shfl_xor(corr, 1, 64);
-  corr += __shfl_xor(corr, 2, 64);
+  for (int o = 1; o < 8; o <<= 1) {
+    s += __shfl_xor(s, o, 64);
+    corr += __shfl_xor(corr, o, 64);
+  }
   if (q == 0) out[i] = s * (g.kappa * g.kappa / (2.0 * PI)) + corr;
 }
 
@@ -347,9 +360,9 @@ void launch_far32_geom(const double* x, const double* y, int64_t N, double kappa
                        double4* grp, double4* pan, float2* rel, hipStream_t s) {
   YQ_REQUIRE(N % Q == 0 && kappa > 0.0, YQ_EINVAL, "far32 geometry: N % 16 != 0 or kappa <= 0");
   const int64_t nt = (N + FT - 1) / FT, ng = (N + FG - 1) / FG, np = N / Q;
-  circles_kernel<<<(unsigned)((nt + 63) / 64), 64, 0, s>>>(x, y, N, FT, nt, tile);
-  circles_kernel<<<(unsigned)((ng + 63) / 64), 64, 0, s>>>(x, y, N, FG, ng, grp);
-  circles_kernel<<<(unsigned)((np + 63) / 64), 64, 0, s>>>(x, y, N, Q, np, pan);
+  circles_kernel<<<(unsigned)((nt + 3) / 4), 256, 0, s>>>(x, y, N, FT, nt, tile);
+  circles_kernel<<<(unsigned)((ng + 3) / 4), 256, 0, s>>>(x, y, N, FG, ng, grp);
+  circles_kernel<<<(unsigned)((np + 3) / 4), 256, 0, s>>>(x, y, N, Q, np, pan);
   rel32_kernel<<<(unsigned)((N + 255) / 256), 256, 0, s>>>(x, y, N, tile, kappa * LOG2E, rel);
   YQ_HIP(hipGetLastError());
 }
@@ -389,7 +402,7 @@ void launch_far_grad64(const GeomView& g, const double* sigma, const FarPlan& fp
 void launch_finish(const GeomView& g, int win, const FarPlan& fp, const double* partial64,
                    const float* partial32, const double* W, const int* xrow, const int* xpan,
                    const double* xvals, const double* sigma, double* out, hipStream_t s) {
-  finish_kernel<<<(unsigned)((4 * g.N + 255) / 256), 256, 0, s>>>(g, win, fp.chunks, partial64,
+  finish_kernel<<<(unsigned)((8 * g.N + 255) / 256), 256, 0, s>>>(g, win, fp.chunks, partial64,
                                                               partial32, W, xrow, xpan, xvals,
                                                               sigma, out);
   YQ_HIP(hipGetLastError());
