@@ -19,13 +19,16 @@ dynamics via efficient integral equation methods" (arXiv 1810.04131):
   graf-coefficient, graf-addition, Theorem qbx-accuracy);
 * dense LU or GMRES for the discrete system (Algorithm 1);
 * the hydrophobic stress, forces and torques (eqs. stress, force_torque,
-  scalar-torque) and the energy of eq. main through Green's first identity.
+  scalar-torque) and the energy of eq. main through Green's first identity;
+* the excluded-volume repulsion of eq. repul with the three-circle ellipse
+  model of supplementary section S1, and the constant-drag forward Euler step
+  of eq. euler (Algorithm 1 without the Stokes mobility solve).
 
 Modules: geometry (panels, nodes, weights), labels (boundary data f),
 kernels (double-layer kernel and its gradient), qbx (near lists, QBX rows,
 oversampled rows), operator (dense matrix and sampled rows), solve (LU and
 MGS-GMRES), forces (surface gradient, traction, F, tau, energy), potential
-(off-surface evaluation).
+(off-surface evaluation), dynamics (repulsion, Euler step).
 
 Readings of points the paper leaves open are listed in each function's
 docstring.  Parity pins live in tests/test_oracle_*.py.
@@ -38,3 +41,4 @@ from .operator import build_matrices, apply_rows, far_rows  # noqa: F401
 from .solve import lu_solve, gmres  # noqa: F401
 from .forces import surface_fields, traction, forces_torques  # noqa: F401
 from .potential import eval_potential  # noqa: F401
+from .dynamics import circle_centres, repulsion, euler_update, time_step  # noqa: F401
