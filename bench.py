@@ -106,6 +106,7 @@ SRC_FOR_COUNTERS = ["paper_1810_04131_amd/csrc/farfield.hip",
                     "paper_1810_04131_amd/csrc/farfield_core.h", "paper_1810_04131_amd/csrc/bessel.h",
                     "paper_1810_04131_amd/csrc/bessel_tables.h"]
 PH_FAR64, PH_FAR32 = 0, 1   # profiling phases of the library (yq_profile_enable)
+PH_QBX, PH_FUSED, PH_REPULSION = 4, 6, 7
 COUNTERS_FILE = "profiles/far32_kernel_50ellipses_N25600_counters.txt"
 PEAK_FP32 = 157.3e12   # published MI355X FP32 vector peak (needs packed FP32)
 PEAK_FP64 = 78.6e12    # published MI355X FP64 vector peak
@@ -122,7 +123,8 @@ def parse():
     ap.add_argument("--fp64-steps", type=int, default=3)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy (counter calibration)")
-    ap.add_argument("--workload", choices=["medium", "batch", "serve", "large", "table2"],
+    ap.add_argument("--workload", choices=["medium", "batch", "serve", "large", "table2",
+                                           "dynamics"],
                     default="medium",
                     help="medium: the 50-ellipse solve (default line); batch: many configurations "
                          "per fused launch; serve: Poisson-arrival continuous batching")
@@ -571,6 +573,76 @@ def bench_table2(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_dynamics(args):
+    """Constant-drag time stepping (eq. euler) of 100 ellipses on a 10 x 10 grid:
+    each step is a warm-started solve, forces, repulsion, Euler update and the
+    set-up rebuild at the new configuration."""
+    import numpy as np
+    import torch
+
+    import paper_1810_04131_amd as yq
+    import workloads
+    cfg = workloads.config_dynamics(seed=0)
+    parts = cfg["particles"]
+    prm = yq.default_params(panels_per_particle=cfg["panels"], qbx_order=cfg["qbx_order"],
+                            tol=cfg["tol"], precision=yq.YQ_MIXED, far_mode=yq.YQ_FAR_AUTO,
+                            maxiter=300)
+    pb = yq.Problem(prm)
+    pb.set_workload(parts)
+    pb.set_boundary_data(pb.boundary_label())
+    dyn = dict(dt=cfg["dt"], xi_x=cfg["xi_x"], xi_theta=cfg["xi_theta"], c0=cfg["c0"],
+               q=cfg["q"], gamma=cfg["gamma"])
+    sigma = torch.zeros(pb.N, dtype=torch.float64, device="cuda")
+    prev = sigma.clone()
+    first = None
+    for k in range(max(args.warmup, 2)):
+        info, _, _, _ = pb.step(sigma, sigma_prev=prev, **dyn)
+        first = first or info["iterations"]
+    lat, its, energy = [], [], []
+    torch.cuda.synchronize()
+    t_all = time.perf_counter()
+    for _ in range(max(args.steps, 1)):
+        t0 = time.perf_counter()
+        info, F, T, E = pb.step(sigma, sigma_prev=prev, **dyn)   # synchronous
+        lat.append(time.perf_counter() - t0)
+        its.append(info["iterations"])
+        energy.append(E[0] + E[1])
+    torch.cuda.synchronize()
+    t_all = time.perf_counter() - t_all
+    # two profiled steps for the breakdown; then a cold solve at the same configuration
+    pb.lib.yq_profile_enable(pb.h, -1)
+    for ph in range(8):
+        prof(pb, ph)
+    for _ in range(2):
+        pb.step(sigma, sigma_prev=prev, **dyn)
+    br = {name: prof(pb, ph) for name, ph in (("inner_far", PH_FAR32), ("fp64_far", PH_FAR64),
+                                              ("fused", PH_FUSED), ("qbx_build", PH_QBX),
+                                              ("repulsion", PH_REPULSION))}
+    pb.lib.yq_profile_enable(pb.h, 0)
+    _, cold = pb.solve()
+    c, a = pb.particles()
+    K = len(lat)
+    out = {
+        "metric": "time steps/s (warm-started solve, forces, repulsion, Euler update, set-up)",
+        "value": K / t_all, "unit": "steps/s", "n_gpus": 1, "steps": K, "warmup": max(args.warmup, 2),
+        "ms_per_step": t_all / K * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": "100 ellipses 1.0x0.5 on a 10x10 grid (spacing 2.5, random "
+                               "orientations), N=51200, kappa=1, QBX order 10, mixed FP32/FP64 "
+                               "tol 1e-8, FMM (far mode auto); dt 0.02, xi_x 1.5, xi_theta 2.0, "
+                               "gamma 1, c0 0.02, q 3; guess 2 sigma_n - sigma_(n-1)",
+                   "N": pb.N, "parallelism": "single GPU"},
+        "latency_ms_p50": percentile(lat, 0.5) * 1e3, "latency_ms_p99": percentile(lat, 0.99) * 1e3,
+        "gmres_iterations_mean": float(np.mean(its)), "gmres_iterations_first_step": first,
+        "gmres_iterations_cold_same_config": cold["iterations"],
+        "total_energy_first_last": [energy[0], energy[-1]],
+        "profiled_step_ms": {k: v[1] / 2 for k, v in br.items()},
+        "repulsion_us_per_launch": br["repulsion"][1] / max(br["repulsion"][0], 1) * 1e3,
+        "particles_moved": float(np.abs(c - parts.center).max()),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.copy_probe:
@@ -588,6 +660,8 @@ def main():
         return bench_large(args)
     if args.workload == "table2":
         return bench_table2(args)
+    if args.workload == "dynamics":
+        return bench_dynamics(args)
     import numpy as np
     import torch
 

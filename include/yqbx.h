@@ -206,6 +206,68 @@ int yq_solve_forces(yq_problem* prob, const double* sigma0, double* sigma, yq_so
 int yq_eval_potential(yq_problem* prob, const double* sigma, int64_t M, const double* tx,
                       const double* ty, double* u);
 
+/* ---- Time stepping ---------------------------------------------------------------------
+ * Excluded-volume repulsion (eq. repul) with the three-circle model of ellipses
+ * (supplementary section S1): particle i is three circles of radius B_i centred
+ * at a_i + k (A_i - B_i) d_i, k = -1, 0, +1, d_i = (cos th_i, sin th_i).  Every
+ * circle pair of two different particles, centre distance r and gap
+ * g = r - (B_i + B_j), repels with (c0/3) q g^-(q+1) along the line of centres
+ * and carries the potential (c0/3) g^-q.  F_i^rep sums the nine pairs over all
+ * other particles, tau_i^rep is the torque about a_i of the forces on the end
+ * circles, Phi_rep sums the potential over unordered pairs.  With A = B the
+ * three circles coincide, so a disk pair repels with 3 times eq. repul's force
+ * for the same c0.  All sums are direct, in FP64.
+ *
+ * The time step is the constant-drag forward Euler law of eq. euler (Algorithm 1
+ * with constant drag coefficients in place of the Stokes mobility solve):
+ *   a_i  += dt / xi_x     (F_i + F_i^rep),
+ *   th_i += dt / xi_theta (tau_i + tau_i^rep),
+ * F_i and tau_i the hydrophobic force and torque of yq_solve_forces. */
+typedef struct yq_dynamics {
+  double dt;        /* time step, >= 0 */
+  double xi_x;      /* translational drag coefficient, > 0 */
+  double xi_theta;  /* rotational drag coefficient, > 0 */
+  double gamma;     /* hydrophobic tension gamma of eq. main */
+  double c0;        /* repulsion strength, >= 0 */
+  int32_t q;        /* repulsion order, 1..16 (3 in two dimensions) */
+} yq_dynamics;
+
+/* Repulsion of the current particles: dev force [2n] F_i^rep, dev torque [n]
+ * tau_i^rep about a_i, host energy (may be NULL) Phi_rep.  c0 >= 0, q in 1..16.
+ * YQ_EGEOM if two circles touch or overlap (an end circle reaches slightly
+ * outside its ellipse near the tips, so close ellipses can be rejected here
+ * although yq_set_particles accepted them).  Synchronous. */
+int yq_repulsion(yq_problem* prob, double c0, int32_t q, double* force, double* torque,
+                 double* energy);
+
+/* One time step.  dev sigma [N]: in, the previous step's density, which
+ * warm-starts GMRES (zeros for a cold start); out, the density at the
+ * configuration the step started from.  dev sigma_prev [N] or NULL: the density
+ * of the step before; with it the initial guess is the linear extrapolation
+ * 2 sigma - sigma_prev, and sigma_prev takes sigma's value on entry, so passing
+ * the same two buffers to every step keeps the history (start both equal).  The step solves eq. bie
+ * there (as yq_solve_forces with dyn->gamma), adds the repulsion, moves every
+ * particle by eq. euler and rebuilds the set-up at the new configuration (as
+ * yq_set_particles with the same semi-axes and kappa).  The boundary data are
+ * kept per node: nodes are fixed in each particle's frame, so a label that is a
+ * function of the polar angle from the director moves with its particle.
+ * dev force [2n] and dev torque [n] (each may be NULL): the total force and
+ * torque that moved the particles.  host energy [2] (may be NULL): Phi and
+ * Phi_rep at the start configuration.  info: host, may be NULL.
+ * YQ_ENOCONV: GMRES stopped above tol; sigma, forces and energies are those of
+ * the last iterate and the particles do not move.  YQ_EGEOM: two repulsion
+ * circles overlap at the start, or the geometry check rejects the new
+ * configuration; the particles do not move (the start configuration's set-up
+ * is rebuilt if needed) and sigma is the start configuration's density.  On
+ * either, sigma_prev has still taken sigma's value on entry.  YQ_EINVAL for
+ * parameters out of range or sigma_prev == sigma (nothing is changed).
+ * Synchronous. */
+int yq_step(yq_problem* prob, const yq_dynamics* dyn, double* sigma, double* sigma_prev,
+            yq_solve_info* info, double* force, double* torque, double* energy);
+
+/* The current particles: host center_xy [2n], host angle [n] (either may be NULL). */
+int yq_get_particles(const yq_problem* prob, double* center_xy, double* angle);
+
 /* ---- Batched solves -------------------------------------------------------------------
  * A batch holds many independent configurations.  Their nodes are laid out one
  * after another (configuration c at offset offsets[c] of every batch vector, in
@@ -331,7 +393,8 @@ int yq_server_cancel(yq_server* server, int64_t ticket);
  * hipEvents on the problem's stream.  Phases: 0 FP64 far field, 1 FP32 far
  * field, 2 finish (chunk sum + near correction), 3 gradient far field, 4 QBX
  * build, 5 Krylov vector kernels, 6 the fused FP64 far field + gradient of
- * yq_solve_forces.  phase_mask: bit p times phase p; 0 times nothing (the
+ * yq_solve_forces, 7 repulsion (and Euler update) of yq_repulsion and yq_step.
+ * phase_mask: bit p times phase p; 0 times nothing (the
  * default); -1 times every phase.  yq_profile_read synchronises the stream and
  * returns the number of timed launches and their summed duration (ms) of one
  * phase; reset != 0 clears that phase. */
@@ -339,7 +402,7 @@ int yq_profile_enable(yq_problem* prob, int32_t phase_mask);
 int yq_profile_read(yq_problem* prob, int32_t phase, int64_t* launches, double* total_ms,
                     int32_t reset);
 
-/* Device special functions (L0), for testing: kind 0 -> K0(z), 1 -> K1(z),
+/* Device special functions, for testing: kind 0 -> K0(z), 1 -> K1(z),
  * 2 -> K_order(z), 3 -> I_order(z); precision YQ_FP64 or YQ_MIXED (FP32).
  * dev z [n] -> dev out [n].  Synchronous. */
 int yq_bessel(int32_t kind, int32_t order, int32_t precision, int64_t n, const double* z, double* out);

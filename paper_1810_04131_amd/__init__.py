@@ -12,7 +12,8 @@ from typing import Optional
 
 from . import _lib
 from ._lib import (YQ_FAR_AUTO, YQ_FAR_DIRECT, YQ_FAR_FMM, YQ_FMM64, YQ_FP64, YQ_LABEL_ARC,  # noqa: F401
-                   YQ_LABEL_JANUS, YQ_M2L_MFMA, YQ_M2L_MFMA64, YQ_M2L_VALU, YQ_MIXED, YQError, yq_params, yq_solve_info)
+                   YQ_LABEL_JANUS, YQ_M2L_MFMA, YQ_M2L_MFMA64, YQ_M2L_VALU, YQ_MIXED, YQError, yq_dynamics, yq_params,
+                   yq_solve_info)
 
 __all__ = ["Problem", "Batch", "Server", "default_params", "bessel", "YQError", "YQ_FP64", "YQ_MIXED"]
 
@@ -170,6 +171,52 @@ class Problem:
         if not (allow_noconv and st == _lib.YQ_ENOCONV):
             self._check(st)
         return out, {k: getattr(info, k) for k, _ in info._fields_}, F.view(self.n, 2), T, e.value
+
+    # -- time stepping ----------------------------------------------------------------------
+    def repulsion(self, c0, q=3):
+        """Excluded-volume repulsion of the current particles (yq_repulsion): F (n, 2), tau, Phi_rep."""
+        F = self._f64(2 * self.n)
+        T = self._f64(self.n)
+        e = ctypes.c_double()
+        self._check(self.lib.yq_repulsion(self.h, float(c0), int(q), _ptr(F), _ptr(T),
+                                          ctypes.byref(e)))
+        return F.view(self.n, 2), T, e.value
+
+    def step(self, sigma, dt, xi_x, xi_theta, c0, q=3, gamma=1.0, sigma_prev=None,
+             allow_noconv=False):
+        """One constant-drag time step (yq_step).
+
+        sigma: device density of length N, the initial guess on entry (the previous
+        step's density) and the density at the start configuration on return
+        (updated in place).  sigma_prev: optional density of the step before; the
+        guess is then 2 sigma - sigma_prev and sigma_prev takes sigma's old value.
+        Returns (info, F_total (n, 2), tau_total, (Phi, Phi_rep)).
+        """
+        for t in (sigma, sigma_prev):
+            if t is not None and not (t.is_contiguous() and t.dtype == self.torch.float64
+                                      and t.device == self.device and t.numel() == self.N):
+                raise ValueError("sigma and sigma_prev must be contiguous float64 device "
+                                 "tensors of length N")
+        dyn = yq_dynamics(float(dt), float(xi_x), float(xi_theta), float(gamma), float(c0), int(q))
+        info = yq_solve_info()
+        F = self._f64(2 * self.n)
+        T = self._f64(self.n)
+        e = (ctypes.c_double * 2)()
+        st = self.lib.yq_step(self.h, ctypes.byref(dyn), _ptr(sigma), _ptr(sigma_prev),
+                              ctypes.byref(info), _ptr(F),
+                              _ptr(T), ctypes.cast(e, ctypes.c_void_p))
+        if not (allow_noconv and st == _lib.YQ_ENOCONV):
+            self._check(st)
+        return {k: getattr(info, k) for k, _ in info._fields_}, F.view(self.n, 2), T, (e[0], e[1])
+
+    def particles(self):
+        """Current centres (n, 2) and angles (n,) as numpy arrays (yq_get_particles)."""
+        import numpy as np
+        c = np.empty(2 * self.n)
+        a = np.empty(self.n)
+        self._check(self.lib.yq_get_particles(self.h, c.ctypes.data_as(ctypes.c_void_p),
+                                              a.ctypes.data_as(ctypes.c_void_p)))
+        return c.reshape(self.n, 2), a
 
     def eval_potential(self, sigma, targets):
         sigma = self._dev(sigma)

@@ -70,6 +70,17 @@ class yq_solve_info(ctypes.Structure):
     ]
 
 
+class yq_dynamics(ctypes.Structure):
+    _fields_ = [
+        ("dt", c_double),
+        ("xi_x", c_double),
+        ("xi_theta", c_double),
+        ("gamma", c_double),
+        ("c0", c_double),
+        ("q", c_int32),
+    ]
+
+
 P = c_void_p  # opaque pointers (problem handles, device pointers)
 
 SIGNATURES = {
@@ -95,6 +106,10 @@ SIGNATURES = {
     "yq_solve_forces": (c_int32, [P, P, P, ctypes.POINTER(yq_solve_info), c_double, P, P,
                                   ctypes.POINTER(c_double)]),
     "yq_eval_potential": (c_int32, [P, P, c_int64, P, P, P]),
+    "yq_repulsion": (c_int32, [P, c_double, c_int32, P, P, ctypes.POINTER(c_double)]),
+    "yq_step": (c_int32, [P, ctypes.POINTER(yq_dynamics), P, P, ctypes.POINTER(yq_solve_info), P,
+                          P, P]),
+    "yq_get_particles": (c_int32, [P, P, P]),
     "yq_bessel": (c_int32, [c_int32, c_int32, c_int32, c_int64, P, P]),
     "yq_batch_create": (c_int32, [ctypes.POINTER(yq_params), ctypes.POINTER(c_void_p)]),
     "yq_batch_destroy": (None, [P]),

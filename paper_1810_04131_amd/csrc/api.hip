@@ -454,236 +454,249 @@ int yq_set_stream(yq_problem* pb, void* stream) {
   });
 }
 
-int yq_set_particles(yq_problem* pb, int32_t n, const double* center_xy, const double* angle,
+}  // extern "C"
+
+namespace {
+
+// The set-up of yq_set_particles (throws yq::Error).  The boundary data buffer
+// keeps its contents when the node count does not change.
+void setup_particles(yq_problem* pb, int32_t n, const double* center_xy, const double* angle,
                      const double* semi_axes, double kappa) {
-  return guarded(pb, [&] {
-    YQ_REQUIRE(pb && center_xy && angle && semi_axes, YQ_EINVAL, "null argument");
-    YQ_REQUIRE(n >= 1, YQ_EINVAL, "need at least one particle");
-    YQ_REQUIRE(std::isfinite(kappa) && kappa > 0.0, YQ_EINVAL, "kappa must be finite and > 0");
-    const int P = pb->prm.panels_per_particle;
-    const int64_t N = (int64_t)n * P * Q;
-    YQ_REQUIRE(N < (int64_t)INT32_MAX, YQ_EINVAL, "too many nodes for one problem");
-    double amax = 0.0;
-    pb->h_pc.assign((size_t)n * 5, 0.0);
-    for (int i = 0; i < n; ++i) {
-      const double cx = center_xy[2 * i], cy = center_xy[2 * i + 1], th = angle[i];
-      const double A = semi_axes[2 * i], B = semi_axes[2 * i + 1];
-      YQ_REQUIRE(std::isfinite(cx) && std::isfinite(cy) && std::isfinite(th) &&
-                     std::isfinite(A) && std::isfinite(B),
-                 YQ_EINVAL, "non-finite particle data");
-      YQ_REQUIRE(B > 0.0 && A >= B, YQ_EINVAL, "semi-axes must satisfy A >= B > 0");
-      double* q = &pb->h_pc[5 * (size_t)i];
-      q[0] = cx;
-      q[1] = cy;
-      q[2] = th;
-      q[3] = A;
-      q[4] = B;
-      amax = std::max(amax, A);
-    }
-    pb->ready = false;
-    pb->pot_fine_ready = false;
-    pb->have_f = false;
-    pb->n = n;
-    pb->N = N;
-    pb->kappa = kappa;
-    hipStream_t s = pb->stream;
+  YQ_REQUIRE(pb && center_xy && angle && semi_axes, YQ_EINVAL, "null argument");
+  YQ_REQUIRE(n >= 1, YQ_EINVAL, "need at least one particle");
+  YQ_REQUIRE(std::isfinite(kappa) && kappa > 0.0, YQ_EINVAL, "kappa must be finite and > 0");
+  const int P = pb->prm.panels_per_particle;
+  const int64_t N = (int64_t)n * P * Q;
+  YQ_REQUIRE(N < (int64_t)INT32_MAX, YQ_EINVAL, "too many nodes for one problem");
+  double amax = 0.0;
+  pb->h_pc.assign((size_t)n * 5, 0.0);
+  for (int i = 0; i < n; ++i) {
+    const double cx = center_xy[2 * i], cy = center_xy[2 * i + 1], th = angle[i];
+    const double A = semi_axes[2 * i], B = semi_axes[2 * i + 1];
+    YQ_REQUIRE(std::isfinite(cx) && std::isfinite(cy) && std::isfinite(th) &&
+                   std::isfinite(A) && std::isfinite(B),
+               YQ_EINVAL, "non-finite particle data");
+    YQ_REQUIRE(B > 0.0 && A >= B, YQ_EINVAL, "semi-axes must satisfy A >= B > 0");
+    double* q = &pb->h_pc[5 * (size_t)i];
+    q[0] = cx;
+    q[1] = cy;
+    q[2] = th;
+    q[3] = A;
+    q[4] = B;
+    amax = std::max(amax, A);
+  }
+  pb->ready = false;
+  pb->pot_fine_ready = false;
+  pb->have_f = false;
+  pb->n = n;
+  pb->N = N;
+  pb->kappa = kappa;
+  hipStream_t s = pb->stream;
 
-    // particle neighbour lists (host): every particle whose ellipse could hold
-    // a near panel of, or overlap, particle p; p itself is included.
-    const double margin = std::max(pb->prm.near_beta, pb->prm.pot_beta) * 2.0 * PI * amax / P *
-                              1.01 + 1e-9;
-    // Candidates come from a uniform grid of cell side 2 amax + margin (no pair
-    // closer than that can be missed); each list is ascending in q.
-    std::vector<int> nbp(n + 1, 0), nbi;
+  // particle neighbour lists (host): every particle whose ellipse could hold
+  // a near panel of, or overlap, particle p; p itself is included.
+  const double margin = std::max(pb->prm.near_beta, pb->prm.pot_beta) * 2.0 * PI * amax / P *
+                            1.01 + 1e-9;
+  // Candidates come from a uniform grid of cell side 2 amax + margin (no pair
+  // closer than that can be missed); each list is ascending in q.
+  std::vector<int> nbp(n + 1, 0), nbi;
+  {
+    double xlo = pb->h_pc[0], ylo = pb->h_pc[1], xhi = xlo, yhi = ylo;
+    for (int p = 0; p < n; ++p) {
+      xlo = std::min(xlo, pb->h_pc[5 * (size_t)p]);
+      xhi = std::max(xhi, pb->h_pc[5 * (size_t)p]);
+      ylo = std::min(ylo, pb->h_pc[5 * (size_t)p + 1]);
+      yhi = std::max(yhi, pb->h_pc[5 * (size_t)p + 1]);
+    }
+    // at most 1024 cells per side (larger cells only add candidates)
+    const double cell = std::max(2.0 * amax + margin, std::max(xhi - xlo, yhi - ylo) / 1024.0);
+    const int64_t gx = std::min<int64_t>((int64_t)((xhi - xlo) / cell) + 1, 1025);
+    const int64_t gy = std::min<int64_t>((int64_t)((yhi - ylo) / cell) + 1, 1025);
+    auto cell_of = [&](double v, double lo, int64_t g) {
+      return std::min<int64_t>(std::max<int64_t>((int64_t)((v - lo) / cell), 0), g - 1);
+    };
+    std::vector<int> head(gx * gy + 1, 0), members(n);
+    std::vector<int64_t> cid(n);
+    for (int p = 0; p < n; ++p) {
+      cid[p] = cell_of(pb->h_pc[5 * (size_t)p], xlo, gx) * gy +
+               cell_of(pb->h_pc[5 * (size_t)p + 1], ylo, gy);
+      ++head[cid[p] + 1];
+    }
+    for (int64_t c = 0; c < gx * gy; ++c) head[c + 1] += head[c];
     {
-      double xlo = pb->h_pc[0], ylo = pb->h_pc[1], xhi = xlo, yhi = ylo;
-      for (int p = 0; p < n; ++p) {
-        xlo = std::min(xlo, pb->h_pc[5 * (size_t)p]);
-        xhi = std::max(xhi, pb->h_pc[5 * (size_t)p]);
-        ylo = std::min(ylo, pb->h_pc[5 * (size_t)p + 1]);
-        yhi = std::max(yhi, pb->h_pc[5 * (size_t)p + 1]);
-      }
-      // at most 1024 cells per side (larger cells only add candidates)
-      const double cell = std::max(2.0 * amax + margin, std::max(xhi - xlo, yhi - ylo) / 1024.0);
-      const int64_t gx = std::min<int64_t>((int64_t)((xhi - xlo) / cell) + 1, 1025);
-      const int64_t gy = std::min<int64_t>((int64_t)((yhi - ylo) / cell) + 1, 1025);
-      auto cell_of = [&](double v, double lo, int64_t g) {
-        return std::min<int64_t>(std::max<int64_t>((int64_t)((v - lo) / cell), 0), g - 1);
-      };
-      std::vector<int> head(gx * gy + 1, 0), members(n);
-      std::vector<int64_t> cid(n);
-      for (int p = 0; p < n; ++p) {
-        cid[p] = cell_of(pb->h_pc[5 * (size_t)p], xlo, gx) * gy +
-                 cell_of(pb->h_pc[5 * (size_t)p + 1], ylo, gy);
-        ++head[cid[p] + 1];
-      }
-      for (int64_t c = 0; c < gx * gy; ++c) head[c + 1] += head[c];
-      {
-        std::vector<int> fill(head.begin(), head.end() - 1);
-        for (int p = 0; p < n; ++p) members[fill[cid[p]]++] = p;
-      }
-      std::vector<int> cand;
-      for (int p = 0; p < n; ++p) {
-        const double* a = &pb->h_pc[5 * (size_t)p];
-        const int64_t cx = cid[p] / gy, cy = cid[p] % gy;
-        cand.clear();
-        for (int64_t ix = std::max<int64_t>(cx - 1, 0); ix <= std::min(cx + 1, gx - 1); ++ix)
-          for (int64_t iy = std::max<int64_t>(cy - 1, 0); iy <= std::min(cy + 1, gy - 1); ++iy)
-            for (int e = head[ix * gy + iy]; e < head[ix * gy + iy + 1]; ++e) {
-              const int q = members[e];
-              const double* b = &pb->h_pc[5 * (size_t)q];
-              const double d = std::hypot(a[0] - b[0], a[1] - b[1]);
-              if (q == p || d < a[3] + b[3] + margin) cand.push_back(q);
-            }
-        std::sort(cand.begin(), cand.end());
-        nbi.insert(nbi.end(), cand.begin(), cand.end());
-        nbp[p + 1] = (int)nbi.size();
-      }
+      std::vector<int> fill(head.begin(), head.end() - 1);
+      for (int p = 0; p < n; ++p) members[fill[cid[p]]++] = p;
     }
-    // host inputs go through pinned staging, so their copies are asynchronous; all
-    // of them complete before the geometry check below returns
-    {
-      const size_t b_pc = pb->h_pc.size() * sizeof(double);
-      const size_t b_np = nbp.size() * sizeof(int), b_ni = nbi.size() * sizeof(int);
-      pb->stage.fit(b_pc + b_np + b_ni + 16);
-      char* st = pb->stage.p;
-      std::memcpy(st, pb->h_pc.data(), b_pc);
-      std::memcpy(st + b_pc, nbp.data(), b_np);
-      if (b_ni) std::memcpy(st + b_pc + b_np, nbi.data(), b_ni);
-      pb->pc.fit(pb->h_pc.size());
-      pb->nb_ptr.fit(nbp.size());
-      pb->nb_idx.fit(std::max<size_t>(nbi.size(), 1));
-      YQ_HIP(hipMemcpyAsync(pb->pc.p, st, b_pc, hipMemcpyHostToDevice, s));
-      YQ_HIP(hipMemcpyAsync(pb->nb_ptr.p, st + b_pc, b_np, hipMemcpyHostToDevice, s));
-      if (b_ni) YQ_HIP(hipMemcpyAsync(pb->nb_idx.p, st + b_pc + b_np, b_ni, hipMemcpyHostToDevice, s));
+    std::vector<int> cand;
+    for (int p = 0; p < n; ++p) {
+      const double* a = &pb->h_pc[5 * (size_t)p];
+      const int64_t cx = cid[p] / gy, cy = cid[p] % gy;
+      cand.clear();
+      for (int64_t ix = std::max<int64_t>(cx - 1, 0); ix <= std::min(cx + 1, gx - 1); ++ix)
+        for (int64_t iy = std::max<int64_t>(cy - 1, 0); iy <= std::min(cy + 1, gy - 1); ++iy)
+          for (int e = head[ix * gy + iy]; e < head[ix * gy + iy + 1]; ++e) {
+            const int q = members[e];
+            const double* b = &pb->h_pc[5 * (size_t)q];
+            const double d = std::hypot(a[0] - b[0], a[1] - b[1]);
+            if (q == p || d < a[3] + b[3] + margin) cand.push_back(q);
+          }
+      std::sort(cand.begin(), cand.end());
+      nbi.insert(nbi.end(), cand.begin(), cand.end());
+      nbp[p + 1] = (int)nbi.size();
     }
+  }
+  // host inputs go through pinned staging, so their copies are asynchronous; all
+  // of them complete before the geometry check below returns
+  {
+    const size_t b_pc = pb->h_pc.size() * sizeof(double);
+    const size_t b_np = nbp.size() * sizeof(int), b_ni = nbi.size() * sizeof(int);
+    pb->stage.fit(b_pc + b_np + b_ni + 16);
+    char* st = pb->stage.p;
+    std::memcpy(st, pb->h_pc.data(), b_pc);
+    std::memcpy(st + b_pc, nbp.data(), b_np);
+    if (b_ni) std::memcpy(st + b_pc + b_np, nbi.data(), b_ni);
+    pb->pc.fit(pb->h_pc.size());
+    pb->nb_ptr.fit(nbp.size());
+    pb->nb_idx.fit(std::max<size_t>(nbi.size(), 1));
+    YQ_HIP(hipMemcpyAsync(pb->pc.p, st, b_pc, hipMemcpyHostToDevice, s));
+    YQ_HIP(hipMemcpyAsync(pb->nb_ptr.p, st + b_pc, b_np, hipMemcpyHostToDevice, s));
+    if (b_ni) YQ_HIP(hipMemcpyAsync(pb->nb_idx.p, st + b_pc + b_np, b_ni, hipMemcpyHostToDevice, s));
+  }
 
-    // a1: nodes, normals, weights; panel arclengths and bounding circles
-    pb->x.alloc(N);
-    pb->y.alloc(N);
-    pb->nx.alloc(N);
-    pb->ny.alloc(N);
-    pb->w.alloc(N);
-    pb->wnx.alloc(N);
-    pb->wny.alloc(N);
-    pb->panel_h.alloc((size_t)n * P);
-    pb->pcx.alloc((size_t)n * P);
-    pb->pcy.alloc((size_t)n * P);
-    pb->pr.alloc((size_t)n * P);
-    GeomView g = pb->view();
-    launch_geometry(g, pb->consts, pb->x.p, pb->y.p, pb->nx.p, pb->ny.p, pb->w.p, pb->wnx.p,
-                    pb->wny.p, s);
-    launch_panel_stats(g, pb->panel_h.p, pb->pcx.p, pb->pcy.p, pb->pr.p, s);
+  // a1: nodes, normals, weights; panel arclengths and bounding circles
+  pb->x.alloc(N);
+  pb->y.alloc(N);
+  pb->nx.alloc(N);
+  pb->ny.alloc(N);
+  pb->w.alloc(N);
+  pb->wnx.alloc(N);
+  pb->wny.alloc(N);
+  pb->panel_h.alloc((size_t)n * P);
+  pb->pcx.alloc((size_t)n * P);
+  pb->pcy.alloc((size_t)n * P);
+  pb->pr.alloc((size_t)n * P);
+  GeomView g = pb->view();
+  launch_geometry(g, pb->consts, pb->x.p, pb->y.p, pb->nx.p, pb->ny.p, pb->w.p, pb->wnx.p,
+                  pb->wny.p, s);
+  launch_panel_stats(g, pb->panel_h.p, pb->pcx.p, pb->pcy.p, pb->pr.p, s);
 
-    // geometry check, and a3: extra near panels per node (count, then their row
-    // offsets by a device scan); one round trip brings back the check and the total
-    pb->bad.alloc(1);
-    YQ_HIP(hipMemsetAsync(pb->bad.p, 0, sizeof(int), s));
-    launch_geom_check(g, pb->nb_ptr.p, pb->nb_idx.p, pb->bad.p, s);
-    pb->xrow.alloc(N + 1);
-    DevBuf<int>& cnt = pb->ncnt;
-    cnt.fit(N);
+  // geometry check, and a3: extra near panels per node (count, then their row
+  // offsets by a device scan); one round trip brings back the check and the total
+  pb->bad.alloc(1);
+  YQ_HIP(hipMemsetAsync(pb->bad.p, 0, sizeof(int), s));
+  launch_geom_check(g, pb->nb_ptr.p, pb->nb_idx.p, pb->bad.p, s);
+  pb->xrow.alloc(N + 1);
+  DevBuf<int>& cnt = pb->ncnt;
+  cnt.fit(N);
+  launch_near_count(g, pb->prm.qbx_window, pb->prm.near_beta, pb->nb_ptr.p, pb->nb_idx.p,
+                    pb->pcx.p, pb->pcy.p, pb->pr.p, cnt.p, nullptr, nullptr, s);
+  launch_row_scan(cnt.p, N, pb->xrow.p, pb->scan_tmp, s);
+  pb->hflags.fit(2 * sizeof(int));
+  int* hfl = (int*)pb->hflags.p;
+  YQ_HIP(hipMemcpyAsync(hfl, pb->bad.p, sizeof(int), hipMemcpyDeviceToHost, s));
+  YQ_HIP(hipMemcpyAsync(hfl + 1, pb->xrow.p + N, sizeof(int), hipMemcpyDeviceToHost, s));
+  YQ_HIP(hipStreamSynchronize(s));
+  YQ_REQUIRE(hfl[0] == 0, YQ_EGEOM, "a node of one particle lies inside another particle");
+  pb->x_total = hfl[1];
+
+  // the FMM tree is built on the host from the node positions; their copy is
+  // queued now so that the QBX build below runs while the tree is built
+  const bool use_fmm = !pb->batch_member &&
+                       (pb->prm.far_mode == YQ_FAR_FMM ||
+                        (pb->prm.far_mode == YQ_FAR_AUTO && N >= kFmmAutoNodes));
+  if (use_fmm) {
+    // the FMM objects of the previous geometry are rebuilt in place: their
+    // device buffers only grow, so a new geometry frees nothing
+    if (!pb->fmm) pb->fmm = std::make_unique<Fmm>();
+    pb->fmm->download(pb->x.p, pb->y.p, pb->wnx.p, pb->wny.p, N, s);
+  }
+
+  // a3: fill the extra near panel lists
+  pb->xpan.fit(std::max<int64_t>(pb->x_total, 1));
+  pb->xvals.fit(std::max<int64_t>(pb->x_total, 1) * Q);
+  pb->xgvals.fit(std::max<int64_t>(pb->x_total, 1) * 2 * Q);
+  if (pb->x_total > 0)
     launch_near_count(g, pb->prm.qbx_window, pb->prm.near_beta, pb->nb_ptr.p, pb->nb_idx.p,
-                      pb->pcx.p, pb->pcy.p, pb->pr.p, cnt.p, nullptr, nullptr, s);
-    launch_row_scan(cnt.p, N, pb->xrow.p, pb->scan_tmp, s);
-    pb->hflags.fit(2 * sizeof(int));
-    int* hfl = (int*)pb->hflags.p;
-    YQ_HIP(hipMemcpyAsync(hfl, pb->bad.p, sizeof(int), hipMemcpyDeviceToHost, s));
-    YQ_HIP(hipMemcpyAsync(hfl + 1, pb->xrow.p + N, sizeof(int), hipMemcpyDeviceToHost, s));
-    YQ_HIP(hipStreamSynchronize(s));
-    YQ_REQUIRE(hfl[0] == 0, YQ_EGEOM, "a node of one particle lies inside another particle");
-    pb->x_total = hfl[1];
+                      pb->pcx.p, pb->pcy.p, pb->pr.p, nullptr, pb->xpan.p, pb->xrow.p, s);
 
-    // the FMM tree is built on the host from the node positions; their copy is
-    // queued now so that the QBX build below runs while the tree is built
-    const bool use_fmm = !pb->batch_member &&
-                         (pb->prm.far_mode == YQ_FAR_FMM ||
-                          (pb->prm.far_mode == YQ_FAR_AUTO && N >= kFmmAutoNodes));
-    if (use_fmm) {
-      // the FMM objects of the previous geometry are rebuilt in place: their
-      // device buffers only grow, so a new geometry frees nothing
-      if (!pb->fmm) pb->fmm = std::make_unique<Fmm>();
-      pb->fmm->download(pb->x.p, pb->y.p, pb->wnx.p, pb->wny.p, N, s);
-    }
+  // a4: QBX correction (window) and oversampled rows (extra near panels)
+  if (!pb->interp_ready) {   // depend on the parameters only
+    upload(pb->Lqbx, interp_for(pb->consts, pb->prm.qbx_oversample), s);
+    upload(pb->Lnear, interp_for(pb->consts, pb->prm.near_oversample), s);
+    upload(pb->Lpot, interp_for(pb->consts, pb->prm.pot_oversample), s);
+    pb->interp_ready = true;
+  }
+  const size_t wsz = (size_t)(2 * pb->prm.qbx_window + 1) * Q * N;
+  pb->W.alloc(wsz);
+  pb->WGx.alloc(wsz);
+  pb->WGy.alloc(wsz);
+  {
+    Timed t(pb, 4);
+    const int qs = pb->prm.qbx_oversample;
+    const size_t nq = (size_t)N * qs;
+    pb->qfx.fit(nq);
+    pb->qfy.fit(nq);
+    pb->qfwx.fit(nq);
+    pb->qfwy.fit(nq);
+    launch_pot_fine(g, pb->consts, qs,
+                    PotFine{qs, pb->qfx.p, pb->qfy.p, pb->qfwx.p, pb->qfwy.p, nullptr}, s);
+    launch_qbx_build(g, pb->prm.qbx_order, pb->prm.qbx_window, qs, pb->prm.qbx_radius,
+                     pb->Lqbx.p, pb->qfx.p, pb->qfy.p, pb->qfwx.p, pb->qfwy.p, pb->W.p,
+                     pb->WGx.p, pb->WGy.p, s);
+  }
+  if (pb->x_total > 0)
+    launch_near_rows(g, pb->consts, pb->prm.near_oversample, pb->Lnear.p, pb->xrow.p,
+                     pb->xpan.p, pb->xvals.p, pb->xgvals.p, s);
 
-    // a3: fill the extra near panel lists
-    pb->xpan.fit(std::max<int64_t>(pb->x_total, 1));
-    pb->xvals.fit(std::max<int64_t>(pb->x_total, 1) * Q);
-    pb->xgvals.fit(std::max<int64_t>(pb->x_total, 1) * 2 * Q);
-    if (pb->x_total > 0)
-      launch_near_count(g, pb->prm.qbx_window, pb->prm.near_beta, pb->nb_ptr.p, pb->nb_idx.p,
-                        pb->pcx.p, pb->pcy.p, pb->pr.p, nullptr, pb->xpan.p, pb->xrow.p, s);
+  // FP32 far field: bounding circles, relative positions, source records
+  pb->ftile.alloc((N + FT - 1) / FT);
+  pb->fgrp.alloc((N + FG - 1) / FG);
+  pb->fpan.alloc(N / Q);
+  pb->frel.alloc(N);
+  pb->fsrc.alloc(N);
+  launch_far32_geom(pb->x.p, pb->y.p, N, kappa, pb->ftile.p, pb->fgrp.p, pb->fpan.p, pb->frel.p,
+                    s);
 
-    // a4: QBX correction (window) and oversampled rows (extra near panels)
-    if (!pb->interp_ready) {   // depend on the parameters only
-      upload(pb->Lqbx, interp_for(pb->consts, pb->prm.qbx_oversample), s);
-      upload(pb->Lnear, interp_for(pb->consts, pb->prm.near_oversample), s);
-      upload(pb->Lpot, interp_for(pb->consts, pb->prm.pot_oversample), s);
-      pb->interp_ready = true;
-    }
-    const size_t wsz = (size_t)(2 * pb->prm.qbx_window + 1) * Q * N;
-    pb->W.alloc(wsz);
-    pb->WGx.alloc(wsz);
-    pb->WGy.alloc(wsz);
-    {
-      Timed t(pb, 4);
-      const int qs = pb->prm.qbx_oversample;
-      const size_t nq = (size_t)N * qs;
-      pb->qfx.fit(nq);
-      pb->qfy.fit(nq);
-      pb->qfwx.fit(nq);
-      pb->qfwy.fit(nq);
-      launch_pot_fine(g, pb->consts, qs,
-                      PotFine{qs, pb->qfx.p, pb->qfy.p, pb->qfwx.p, pb->qfwy.p, nullptr}, s);
-      launch_qbx_build(g, pb->prm.qbx_order, pb->prm.qbx_window, qs, pb->prm.qbx_radius,
-                       pb->Lqbx.p, pb->qfx.p, pb->qfy.p, pb->qfwx.p, pb->qfwy.p, pb->W.p,
-                       pb->WGx.p, pb->WGy.p, s);
-    }
-    if (pb->x_total > 0)
-      launch_near_rows(g, pb->consts, pb->prm.near_oversample, pb->Lnear.p, pb->xrow.p,
-                       pb->xpan.p, pb->xvals.p, pb->xgvals.p, s);
-
-    // FP32 far field: bounding circles, relative positions, source records
-    pb->ftile.alloc((N + FT - 1) / FT);
-    pb->fgrp.alloc((N + FG - 1) / FG);
-    pb->fpan.alloc(N / Q);
-    pb->frel.alloc(N);
-    pb->fsrc.alloc(N);
-    launch_far32_geom(pb->x.p, pb->y.p, N, kappa, pb->ftile.p, pb->fgrp.p, pb->fpan.p, pb->frel.p,
-                      s);
-
-    pb->fp = far_plan(N, N, 256, pb->far_want);
-    if (use_fmm) {
-      pb->fmm->use_mfma = pb->prm.fmm_m2l != YQ_M2L_VALU;
-      pb->fmm->want_m2l32 = pb->prm.fmm_m2l == YQ_M2L_MFMA;
-      pb->fmm->build(N, kappa, pb->prm.fmm_order, pb->prm.fmm_leaf_max, pb->tab.p, s);
-      if (pb->prm.fmm_resid_order > 0) {
-        if (!pb->fmm_hi) pb->fmm_hi = std::make_unique<Fmm>();
-        pb->fmm_hi->use_mfma = pb->prm.fmm_m2l != YQ_M2L_VALU;
-        pb->fmm_hi->want_m2l32 = false;
-        pb->fmm_hi->copy_tree(*pb->fmm, pb->prm.fmm_resid_order, pb->tab.p, s);
-      } else {
-        pb->fmm_hi.reset();
-      }
+  pb->fp = far_plan(N, N, 256, pb->far_want);
+  if (use_fmm) {
+    pb->fmm->use_mfma = pb->prm.fmm_m2l != YQ_M2L_VALU;
+    pb->fmm->want_m2l32 = pb->prm.fmm_m2l == YQ_M2L_MFMA;
+    pb->fmm->build(N, kappa, pb->prm.fmm_order, pb->prm.fmm_leaf_max, pb->tab.p, s);
+    if (pb->prm.fmm_resid_order > 0) {
+      if (!pb->fmm_hi) pb->fmm_hi = std::make_unique<Fmm>();
+      pb->fmm_hi->use_mfma = pb->prm.fmm_m2l != YQ_M2L_VALU;
+      pb->fmm_hi->want_m2l32 = false;
+      pb->fmm_hi->copy_tree(*pb->fmm, pb->prm.fmm_resid_order, pb->tab.p, s);
     } else {
-      pb->fmm.reset();
       pb->fmm_hi.reset();
     }
-    pb->partial.alloc((size_t)pb->fp.chunks * N);
-    pb->partial32.alloc((size_t)pb->fp.chunks * N);
-    pb->f.alloc(N);
-    pb->en.alloc(n);
-    if (!pb->batch_member) {
-      pb->gpartial.alloc((size_t)pb->fp.chunks * 2 * N);
-      pb->gx.alloc(N);
-      pb->gy.alloc(N);
-      ensure_krylov(pb);
-    }
-    // the rest of the set-up stays queued on the problem's stream, ahead of any
-    // later work of the problem; batch members are read from the batch's stream
-    if (pb->batch_member) YQ_HIP(hipStreamSynchronize(s));
-    pb->ready = true;
-  });
+  } else {
+    pb->fmm.reset();
+    pb->fmm_hi.reset();
+  }
+  pb->partial.alloc((size_t)pb->fp.chunks * N);
+  pb->partial32.alloc((size_t)pb->fp.chunks * N);
+  pb->f.alloc(N);
+  pb->en.alloc(n);
+  if (!pb->batch_member) {
+    pb->gpartial.alloc((size_t)pb->fp.chunks * 2 * N);
+    pb->gx.alloc(N);
+    pb->gy.alloc(N);
+    ensure_krylov(pb);
+  }
+  // the rest of the set-up stays queued on the problem's stream, ahead of any
+  // later work of the problem; batch members are read from the batch's stream
+  if (pb->batch_member) YQ_HIP(hipStreamSynchronize(s));
+  pb->ready = true;
+}
+
+}  // namespace
+
+extern "C" {
+
+int yq_set_particles(yq_problem* pb, int32_t n, const double* center_xy, const double* angle,
+                     const double* semi_axes, double kappa) {
+  return guarded(pb, [&] { setup_particles(pb, n, center_xy, angle, semi_axes, kappa); });
 }
 
 int yq_num_nodes(const yq_problem* pb, int64_t* N) {
@@ -1024,6 +1037,161 @@ int yq_eval_potential(yq_problem* pb, const double* sigma, int64_t M, const doub
     launch_potential(g, pf, pb->Lpot.p, pb->prm.pot_beta, sigma, M, tx, ty, pp,
                      pb->pot_partial.p, u, pb->stream);
   });
+}
+
+}  // extern "C"
+
+namespace {
+
+void check_repulsion(double c0, int32_t q) {
+  YQ_REQUIRE(std::isfinite(c0) && c0 >= 0.0, YQ_EINVAL, "c0 must be finite and >= 0");
+  YQ_REQUIRE(q >= 1 && q <= 16, YQ_EINVAL, "repulsion order q out of range 1..16");
+}
+
+// Repulsion of the current particles (eq. repul, three circles per ellipse);
+// with update, also the Euler update of eq. euler from the hydrophobic force
+// and torque fh, th into pb->dpnew, which is then on the host in
+// pb->dstage after the n potential partials.  Returns Phi_rep.
+double repulsion_of(yq_problem* pb, double c0, int32_t q, const double* fh, const double* th,
+                    double dtx, double dtt, double* force, double* torque, bool update) {
+  const int n = pb->n;
+  hipStream_t s = pb->stream;
+  pb->dcc.fit(n);
+  pb->drad.fit(n);
+  pb->dphi.fit(n);
+  pb->dbad.fit(1);
+  if (update) pb->dpnew.fit((size_t)3 * n);
+  YQ_HIP(hipMemsetAsync(pb->dbad.p, 0, sizeof(int), s));
+  {
+    Timed t(pb, 7);
+    launch_circles3(pb->pc.p, n, pb->dcc.p, pb->drad.p, s);
+    DynArgs a{};
+    a.pc = pb->pc.p;
+    a.cc = pb->dcc.p;
+    a.rad = pb->drad.p;
+    a.n = n;
+    a.q = q;
+    a.c3 = c0 / 3.0;
+    a.fh = fh;
+    a.th = th;
+    a.dtx = dtx;
+    a.dtt = dtt;
+    a.force = force;
+    a.torque = torque;
+    a.phi = pb->dphi.p;
+    a.pnew = update ? pb->dpnew.p : nullptr;
+    a.bad = pb->dbad.p;
+    launch_repulsion(a, s);
+  }
+  // one round trip: the potential partials, the new configuration, the flag
+  const size_t nd = (size_t)n * (update ? 4 : 1);
+  pb->dstage.fit(nd * sizeof(double) + sizeof(double));
+  double* h = (double*)pb->dstage.p;
+  YQ_HIP(hipMemcpyAsync(h, pb->dphi.p, n * sizeof(double), hipMemcpyDeviceToHost, s));
+  if (update)
+    YQ_HIP(hipMemcpyAsync(h + n, pb->dpnew.p, 3 * (size_t)n * sizeof(double),
+                          hipMemcpyDeviceToHost, s));
+  int* hb = (int*)(h + nd);
+  YQ_HIP(hipMemcpyAsync(hb, pb->dbad.p, sizeof(int), hipMemcpyDeviceToHost, s));
+  YQ_HIP(hipStreamSynchronize(s));
+  YQ_REQUIRE(*hb == 0, YQ_EGEOM, "two circles of the repulsion model touch or overlap");
+  double t = 0.0;
+  for (int i = 0; i < n; ++i) t += h[i];
+  return 0.5 * t;
+}
+
+}  // namespace
+
+extern "C" {
+
+int yq_repulsion(yq_problem* pb, double c0, int32_t q, double* force, double* torque,
+                 double* energy) {
+  return guarded(pb, [&] {
+    require_ready(pb);
+    YQ_REQUIRE(force && torque, YQ_EINVAL, "null argument");
+    check_repulsion(c0, q);
+    const double e = repulsion_of(pb, c0, q, nullptr, nullptr, 0.0, 0.0, force, torque, false);
+    if (energy) *energy = e;
+  });
+}
+
+int yq_get_particles(const yq_problem* pb, double* center_xy, double* angle) {
+  if (!pb) return YQ_EINVAL;
+  if (pb->h_pc.empty()) return YQ_ESTATE;
+  for (int i = 0; i < pb->n; ++i) {
+    if (center_xy) {
+      center_xy[2 * i] = pb->h_pc[5 * (size_t)i];
+      center_xy[2 * i + 1] = pb->h_pc[5 * (size_t)i + 1];
+    }
+    if (angle) angle[i] = pb->h_pc[5 * (size_t)i + 2];
+  }
+  return YQ_OK;
+}
+
+int yq_step(yq_problem* pb, const yq_dynamics* dyn, double* sigma, double* sigma_prev,
+            yq_solve_info* info, double* force, double* torque, double* energy) {
+  int rc = guarded(pb, [&] {
+    require_ready(pb);
+    YQ_REQUIRE(dyn && sigma, YQ_EINVAL, "null argument");
+    YQ_REQUIRE(sigma_prev != sigma, YQ_EINVAL, "sigma_prev aliases sigma");
+    YQ_REQUIRE(pb->have_f, YQ_ESTATE, "boundary data not set");
+    YQ_REQUIRE(std::isfinite(dyn->dt) && dyn->dt >= 0.0, YQ_EINVAL, "dt must be finite and >= 0");
+    YQ_REQUIRE(std::isfinite(dyn->xi_x) && dyn->xi_x > 0.0 && std::isfinite(dyn->xi_theta) &&
+                   dyn->xi_theta > 0.0,
+               YQ_EINVAL, "drag coefficients must be finite and > 0");
+    YQ_REQUIRE(std::isfinite(dyn->gamma), YQ_EINVAL, "gamma must be finite");
+    check_repulsion(dyn->c0, dyn->q);
+    pb->dfh.fit((size_t)2 * pb->n);
+    pb->dth.fit(pb->n);
+    if (sigma_prev) launch_predict(sigma, sigma_prev, pb->N, pb->stream);
+  });
+  if (rc != YQ_OK) return rc;
+  // solve at the current configuration, warm-started from sigma, and its forces
+  double e_h = 0.0;
+  const int st = yq_solve_forces(pb, sigma, sigma, info, dyn->gamma, pb->dfh.p, pb->dth.p, &e_h);
+  if (st != YQ_OK && st != YQ_ENOCONV) return st;
+  rc = guarded(pb, [&] {
+    const bool move = st == YQ_OK;
+    const int n = pb->n;
+    const double e_r = repulsion_of(pb, dyn->c0, dyn->q, pb->dfh.p, pb->dth.p,
+                                    dyn->dt / dyn->xi_x, dyn->dt / dyn->xi_theta, force, torque,
+                                    move);
+    if (energy) {
+      energy[0] = e_h;
+      energy[1] = e_r;
+    }
+    if (!move) return;
+    // the new configuration; the boundary data stay, node k keeping its value
+    const double* h = (const double*)pb->dstage.p + n;
+    std::vector<double> cxy(2 * (size_t)n), ang(n), ax(2 * (size_t)n), ocxy(2 * (size_t)n),
+        oang(n);
+    for (int i = 0; i < n; ++i) {
+      const double* o = &pb->h_pc[5 * (size_t)i];
+      cxy[2 * i] = h[3 * i];
+      cxy[2 * i + 1] = h[3 * i + 1];
+      ang[i] = h[3 * i + 2];
+      ax[2 * i] = o[3];
+      ax[2 * i + 1] = o[4];
+      ocxy[2 * i] = o[0];
+      ocxy[2 * i + 1] = o[1];
+      oang[i] = o[2];
+    }
+    const double kappa = pb->kappa;
+    try {
+      setup_particles(pb, n, cxy.data(), ang.data(), ax.data(), kappa);
+    } catch (const Error& e) {
+      if (e.code != YQ_EGEOM) throw;
+      // rejected: rebuild the configuration the step started from
+      setup_particles(pb, n, ocxy.data(), oang.data(), ax.data(), kappa);
+      pb->have_f = true;
+      throw Error{YQ_EGEOM, "the updated configuration was rejected (" + e.msg +
+                                "); the particles did not move"};
+    }
+    pb->have_f = true;
+  });
+  if (rc != YQ_OK) return rc;
+  if (st != YQ_OK) pb->err = "GMRES did not reach the tolerance; the particles did not move";
+  return st;
 }
 
 int yq_profile_enable(yq_problem* pb, int32_t phase_mask) {

@@ -277,6 +277,28 @@ void launch_update(double* w, const double* V, int64_t ld, int k, const double* 
 void launch_axpby(double a, const double* x, double b, const double* y, double* out, int64_t n,
                   hipStream_t s);
 
+// excluded-volume repulsion and the Euler update (dynamics.hip)
+struct DynArgs {
+  const double* pc;    // [5n] particles (cx, cy, theta, A, B)
+  const double4* cc;   // [n] centre and h d of the three circles (launch_circles3)
+  const double* rad;   // [n] circle radius B
+  int n;
+  int q;               // repulsion order
+  double c3;           // c0 / 3, the strength of one circle pair
+  const double* fh;    // [2n] hydrophobic force added before the update, or null
+  const double* th;    // [n] hydrophobic torque, with fh
+  double dtx, dtt;     // dt / xi_x and dt / xi_theta
+  double* force;       // [2n] out: total force (F^rep + fh), or null
+  double* torque;      // [n] out: total torque, or null
+  double* phi;         // [n] out: sum over the circle pairs of particle i of (c0/3) g^-q
+  double* pnew;        // [3n] out: updated (cx, cy, theta), or null
+  int* bad;            // set to 1 when two circles touch or overlap
+};
+void launch_circles3(const double* pc, int n, double4* cc, double* rad, hipStream_t s);
+void launch_repulsion(const DynArgs& a, hipStream_t s);
+// sigma <- 2 sigma - sigma_prev, sigma_prev <- the old sigma
+void launch_predict(double* sigma, double* sigma_prev, int64_t N, hipStream_t s);
+
 // post-processing (post.hip)
 void launch_forces(const GeomView& g, const double* f, const double* gx, const double* gy,
                    double gamma, double* force, double* torque, double* energy_part,

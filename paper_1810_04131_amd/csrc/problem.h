@@ -63,10 +63,16 @@ struct yq_problem {
   const double* src_for = nullptr; // fsrc already holds the FP32 records of this vector
   DevBuf<double> gx, gy, en;
   DevBuf<double> delta;   // refinement correction
+  // time stepping: circles of the repulsion model, per-particle potential, new
+  // configuration, hydrophobic force and torque of the step, overlap flag
+  DevBuf<double4> dcc;
+  DevBuf<double> drad, dphi, dpnew, dfh, dth;
+  DevBuf<int> dbad;
+  PinnedBuf dstage;
   bool grad_ready = false;  // gpartial holds the direct gradient far field of the solve's sigma
 
   // per-phase timers
-  static constexpr int NPHASE = 7;
+  static constexpr int NPHASE = 8;
   uint32_t prof_mask = 0;   // bit p: time the launches of phase p
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[NPHASE];
   std::vector<hipEvent_t> pool;

@@ -33,6 +33,8 @@ __all__ = [
     "batched_configs",
     "serving_trace",
     "single_disk",
+    "grid_ellipses",
+    "config_dynamics",
     "random_density",
 ]
 
@@ -162,6 +164,21 @@ def single_disk(radius: float = 1.0, kappa: float = 0.25, angle: float = 0.0,
                      np.array([[radius, radius]]), float(kappa), "disk")
 
 
+def grid_ellipses(nx: int = 10, ny: int = 10, spacing: float = 2.5, kappa: float = 1.0,
+                  seed: int = 0, axes=(1.0, 0.5)) -> Particles:
+    """nx x ny ellipses on a square grid with uniformly random orientations (the
+    constant-drag movie of the supplement: 100 particles on a 10 x 10 grid).
+
+    With spacing > 2 A no two ellipses, and no two circles of the three-circle
+    repulsion model (each reaches at most A from its centre), can touch."""
+    rng = np.random.default_rng(seed)
+    gx, gy = np.meshgrid(np.arange(nx) * spacing, np.arange(ny) * spacing, indexing="xy")
+    center = np.stack([gx.ravel(), gy.ravel()], axis=1).astype(np.float64)
+    angle = rng.uniform(0.0, 2.0 * np.pi, size=nx * ny)
+    ax = np.tile(np.asarray(axes, dtype=np.float64), (nx * ny, 1))
+    return Particles(center, angle, ax, float(kappa), f"{nx}x{ny} grid, spacing {spacing}, seed {seed}")
+
+
 # --- the named workloads -------------------------------------------------------------------
 
 def config_small(seed: int = 0) -> dict:
@@ -182,6 +199,20 @@ def config_large(seed: int = 0) -> dict:
     p = random_ellipses(500, 100.0, 1.0, seed, gap=0.2, axes_range=((0.8, 1.2), (0.4, 0.6)))
     return dict(particles=p, panels=32, qbx_order=10, tol=1e-8, fmm_order=20, fmm_leaf=64,
                 name="500 ellipses N=256000")
+
+
+def config_dynamics(seed: int = 0) -> dict:
+    """100 ellipses 1.0x0.5 on a 10x10 grid of spacing 2.5 with random orientations,
+    32 panels x 16 nodes (N=51,200), kappa=1, QBX order 10, FMM far field (far mode
+    AUTO), linear extrapolation of the density as GMRES's guess; constant-drag time
+    stepping with the supplement's movie drags xi_x = 1.5, xi_theta = 2.0, gamma = 1,
+    repulsion c0 = 0.02, q = 3 and dt = 0.02.  Forward Euler is stable while
+    2 k dt / xi_x < 2 for the relative motion of the closest pair, k = 4 c0 / g^5 the
+    stiffness of one circle pair; the trajectory settles at gaps near 0.3, where
+    dt = 0.02 keeps 2 k dt / xi_x near 1 (dt = 0.05 oscillates there)."""
+    p = grid_ellipses(10, 10, 2.5, 1.0, seed)
+    return dict(particles=p, panels=32, qbx_order=10, tol=1e-8, dt=0.02, xi_x=1.5, xi_theta=2.0,
+                gamma=1.0, c0=0.02, q=3, name="100 ellipses on a 10x10 grid, N=51200")
 
 
 def batched_configs(count: int, seed: int = 0, nmin: int = 10, nmax: int = 200,
