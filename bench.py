@@ -124,7 +124,7 @@ def parse():
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy (counter calibration)")
     ap.add_argument("--workload", choices=["medium", "batch", "serve", "large", "table2",
-                                           "dynamics"],
+                                           "dynamics", "cutoff"],
                     default="medium",
                     help="medium: the 50-ellipse solve (default line); batch: many configurations "
                          "per fused launch; serve: Poisson-arrival continuous batching")
@@ -643,6 +643,73 @@ def bench_dynamics(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_cutoff(args):
+    """The cutoff far field (sums truncated where exp(-kappa r) is below the bound,
+    cutoff_tol 1e-12) beside the exact direct sum on the 50-ellipse workload at
+    kappa 1, 2 and 4, and beside the FMM on the 500-ellipse workload at kappa 4.
+    One step = set-up + label + mixed solve to 1e-8 + forces."""
+    import numpy as np
+    import torch
+
+    import paper_1810_04131_amd as yq
+    import workloads
+
+    def run(parts, kw, steps):
+        pb = yq.Problem(yq.default_params(**kw))
+        lat, out = [], None
+        for k in range(max(args.warmup, 1) + steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            pb.set_workload(parts)
+            pb.set_boundary_data(pb.boundary_label())
+            out = pb.solve_forces(allow_noconv=True)
+            torch.cuda.synchronize()
+            if k >= max(args.warmup, 1):
+                lat.append(time.perf_counter() - t0)
+        pb.lib.yq_profile_enable(pb.h, (1 << PH_FAR32) | (1 << PH_FAR64))
+        for ph in range(8):
+            prof(pb, ph)
+        pb.set_workload(parts)
+        pb.set_boundary_data(pb.boundary_label())
+        pb.solve_forces(allow_noconv=True)
+        n32, ms32 = prof(pb, PH_FAR32)
+        n64, ms64 = prof(pb, PH_FAR64)
+        info = out[1]
+        return {"ms_per_step": percentile(lat, 0.5) * 1e3, "gmres_iterations": info["iterations"],
+                "residual": info["residual"], "inner_far_ms": ms32 / max(n32, 1),
+                "fp64_far_ms": ms64 / max(n64, 1)}, out[2].cpu().numpy()
+
+    steps = max(min(args.steps, 5), 1)
+    rows = []
+    base = dict(panels_per_particle=32, qbx_order=10, tol=1e-8, precision=yq.YQ_MIXED, maxiter=300)
+    for kappa in (1.0, 2.0, 4.0):
+        parts = workloads.config_medium(kappa=kappa, seed=0)["particles"]
+        rd, Fd = run(parts, base, steps)
+        rc, Fc = run(parts, dict(base, far_mode=yq.YQ_FAR_CUTOFF, cutoff_tol=1e-12), steps)
+        rows.append({"workload": f"50 ellipses N=25600 kappa={kappa:g}", "direct": rd, "cutoff": rc,
+                     "force_rel_diff": float(np.abs(Fc - Fd).max() / np.abs(Fd).max())})
+    large = workloads.config_large(seed=0)["particles"].copy()
+    large.kappa = 4.0
+    lbase = dict(base, maxiter=400)
+    rf, Ff = run(large, dict(lbase, far_mode=yq.YQ_FAR_FMM, fmm_order=20, fmm_leaf_max=64,
+                             fmm_resid_order=40), steps)
+    rc, Fc = run(large, dict(lbase, far_mode=yq.YQ_FAR_CUTOFF, cutoff_tol=1e-12), steps)
+    rows.append({"workload": "500 ellipses N=256000 kappa=4", "fmm": rf, "cutoff": rc,
+                 "force_rel_diff": float(np.abs(Fc - Ff).max() / np.abs(Ff).max())})
+    out = {
+        "metric": "solve-and-forces steps/s with the cutoff far field (500 ellipses, N=256000, kappa 4)",
+        "value": 1e3 / rc["ms_per_step"], "unit": "steps/s", "n_gpus": 1, "steps": steps,
+        "warmup": max(args.warmup, 1), "ms_per_step": rc["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": "cutoff far field (cutoff_tol 1e-12; FP32 inner operator 1e-7) vs the "
+                               "exact direct sum (50 ellipses, kappa 1/2/4) and vs the FMM (500 "
+                               "ellipses, kappa 4, order 20 inner / 40 residual); mixed tol 1e-8",
+                   "parallelism": "single GPU"},
+        "rows": rows,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.copy_probe:
@@ -662,6 +729,8 @@ def main():
         return bench_table2(args)
     if args.workload == "dynamics":
         return bench_dynamics(args)
+    if args.workload == "cutoff":
+        return bench_cutoff(args)
     import numpy as np
     import torch
 

@@ -54,7 +54,7 @@ enum {
 
 enum { YQ_FP64 = 0, YQ_MIXED = 1 };                       /* precision */
 enum { YQ_FMM64 = 2 };  /* yq_apply_far only: FMM expansions with FP64 near interactions */
-enum { YQ_FAR_DIRECT = 0, YQ_FAR_FMM = 1, YQ_FAR_AUTO = 2 };   /* far-field mode */
+enum { YQ_FAR_DIRECT = 0, YQ_FAR_FMM = 1, YQ_FAR_AUTO = 2, YQ_FAR_CUTOFF = 3 };   /* far-field mode */
 enum { YQ_LABEL_ARC = 0, YQ_LABEL_JANUS = 1 };             /* boundary labels */
 enum { YQ_M2L_MFMA = 0, YQ_M2L_VALU = 1, YQ_M2L_MFMA64 = 2 };   /* FMM translation kernels */
 
@@ -71,7 +71,8 @@ typedef struct yq_params {
   int32_t pot_oversample;      /* sub-panels for off-surface targets near a panel (1..16) */
   double pot_beta;             /* off-surface near criterion, as near_beta */
   int32_t precision;           /* YQ_FP64, or YQ_MIXED: FP32 far field inside FP64 refinement */
-  int32_t far_mode;            /* YQ_FAR_DIRECT | YQ_FAR_FMM | YQ_FAR_AUTO (FMM from 20000 nodes) */
+  int32_t far_mode;            /* YQ_FAR_DIRECT | YQ_FAR_FMM | YQ_FAR_AUTO (FMM from 20000 nodes) |
+                                  YQ_FAR_CUTOFF (direct sums truncated at a radius, cutoff_tol) */
   int32_t fmm_order;           /* FMM expansion order (far_mode FMM) */
   int32_t fmm_leaf_max;        /* nodes per quadtree leaf (far_mode FMM) */
   double tol;                  /* GMRES: stop at ||f - A sigma||_2 / ||f||_2 <= tol */
@@ -88,6 +89,18 @@ typedef struct yq_params {
                                   translations FP64 on the matrix cores) or YQ_M2L_VALU (FP64, one
                                   lane per coefficient; the same results as YQ_M2L_MFMA64 to
                                   rounding) */
+  double cutoff_tol;           /* YQ_FAR_CUTOFF: bound eps on the far-field truncation.  The kernel
+                                  decays like exp(-kappa r) (eq. exp_decay), so a pair at distance r
+                                  contributes at most w_j |sigma_j| kappa K1(kappa r) / (2 pi).  The
+                                  sums skip every (64-target group, 256-source tile) pair whose
+                                  bounding circles are at least z_c / kappa apart, z_c the smallest z
+                                  with kappa/(2 pi) sqrt(pi/(2z)) e^-z (1 + 3/(8z)) L <= eps
+                                  (DLMF 10.40.10 bounds K1(z) by the first two terms), L = 2 pi sum_i
+                                  A_i >= the total perimeter.  So the skipped part of every far-field
+                                  value is <= eps ||sigma||_inf, and with the extra factor (1 + 3/z)
+                                  of the gradient bound that of every gradient <= eps kappa
+                                  ||sigma||_inf.  The FP32 inner operator of YQ_MIXED uses
+                                  max(eps, inner_tol / 10).  0 < cutoff_tol < 1 */
 } yq_params;
 
 typedef struct yq_solve_info {
@@ -102,7 +115,7 @@ typedef struct yq_solve_info {
 /* Defaults: P = 32, p = 10, window 2, oversample 4, radius 0.25, near_beta 0.5,
  * near_oversample 4, pot_oversample 8, pot_beta 0.5, FP64, direct far field,
  * FMM order 20 / 64 per leaf, tol 1e-10, maxiter 200, restart 100,
- * inner_tol 1e-6, max_refine 8, fmm_resid_order 40, fmm_m2l YQ_M2L_MFMA. */
+ * inner_tol 1e-6, max_refine 8, fmm_resid_order 40, fmm_m2l YQ_M2L_MFMA, cutoff_tol 1e-12. */
 void yq_default_params(yq_params* params);
 
 /* Creates a problem on the current HIP device.  params: host, copied. */

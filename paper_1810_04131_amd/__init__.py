@@ -11,7 +11,7 @@ import ctypes
 from typing import Optional
 
 from . import _lib
-from ._lib import (YQ_FAR_AUTO, YQ_FAR_DIRECT, YQ_FAR_FMM, YQ_FMM64, YQ_FP64, YQ_LABEL_ARC,  # noqa: F401
+from ._lib import (YQ_FAR_AUTO, YQ_FAR_CUTOFF, YQ_FAR_DIRECT, YQ_FAR_FMM, YQ_FMM64, YQ_FP64, YQ_LABEL_ARC,  # noqa: F401
                    YQ_LABEL_JANUS, YQ_M2L_MFMA, YQ_M2L_MFMA64, YQ_M2L_VALU, YQ_MIXED, YQError, yq_dynamics, yq_params,
                    yq_solve_info)
 

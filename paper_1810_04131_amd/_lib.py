@@ -21,6 +21,7 @@ YQ_FMM64 = 2
 YQ_FAR_DIRECT = 0
 YQ_FAR_FMM = 1
 YQ_FAR_AUTO = 2
+YQ_FAR_CUTOFF = 3
 YQ_LABEL_ARC = 0
 YQ_LABEL_JANUS = 1
 YQ_M2L_MFMA = 0
@@ -56,6 +57,7 @@ class yq_params(ctypes.Structure):
         ("max_refine", c_int32),
         ("fmm_resid_order", c_int32),
         ("fmm_m2l", c_int32),
+        ("cutoff_tol", c_double),
     ]
 
 

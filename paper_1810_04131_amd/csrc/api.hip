@@ -87,8 +87,11 @@ void check_params(const yq_params& p) {
   YQ_REQUIRE(p.qbx_radius > 0.0 && p.qbx_radius < 1.0, YQ_EINVAL, "qbx_radius must be in (0, 1)");
   YQ_REQUIRE(p.near_beta >= 0.0 && p.pot_beta >= 0.0, YQ_EINVAL, "near_beta, pot_beta >= 0");
   YQ_REQUIRE(p.precision == YQ_FP64 || p.precision == YQ_MIXED, YQ_EINVAL, "bad precision");
-  YQ_REQUIRE(p.far_mode == YQ_FAR_DIRECT || p.far_mode == YQ_FAR_FMM || p.far_mode == YQ_FAR_AUTO,
+  YQ_REQUIRE(p.far_mode == YQ_FAR_DIRECT || p.far_mode == YQ_FAR_FMM || p.far_mode == YQ_FAR_AUTO ||
+                 p.far_mode == YQ_FAR_CUTOFF,
              YQ_EINVAL, "bad far_mode");
+  YQ_REQUIRE(p.far_mode != YQ_FAR_CUTOFF || (p.cutoff_tol > 0.0 && p.cutoff_tol < 1.0), YQ_EINVAL,
+             "cutoff_tol must be in (0, 1)");
   YQ_REQUIRE(p.fmm_order >= 1 && p.fmm_order <= MAXP_FMM, YQ_EINVAL, "fmm_order out of range 1..48");
   YQ_REQUIRE(p.fmm_resid_order >= 0 && p.fmm_resid_order <= MAXP_FMM, YQ_EINVAL,
              "fmm_resid_order out of range 0..48");
@@ -406,6 +409,7 @@ void yq_default_params(yq_params* p) {
   p->max_refine = 8;
   p->fmm_resid_order = 40;
   p->fmm_m2l = YQ_M2L_MFMA;
+  p->cutoff_tol = 1e-12;
 }
 
 const char* yq_error_string(int status) {
@@ -457,6 +461,25 @@ int yq_set_stream(yq_problem* pb, void* stream) {
 }  // extern "C"
 
 namespace {
+
+// Cutoff far field: the smallest z with kappa/(2 pi) sqrt(pi/(2z)) e^-z (1 + 3/(8z)) L
+// (times 1 + 3/z for the gradient) <= eps.  The left side bounds kappa K1(z) L / (2 pi)
+// (DLMF 10.40.10: the remainder after the 3/(8z) term is negative for z > 0) and
+// decreases in z, so bisection finds it.
+double cutoff_z(double kappa, double L, double eps, bool grad) {
+  auto bound = [&](double z) {
+    double b = kappa / (2.0 * PI) * std::sqrt(PI / (2.0 * z)) * std::exp(-z) *
+               (1.0 + 3.0 / (8.0 * z)) * L;
+    return grad ? b * (1.0 + 3.0 / z) : b;
+  };
+  double lo = 1e-3, hi = 2000.0;
+  if (bound(lo) <= eps) return lo;
+  for (int it = 0; it < 200 && hi - lo > 1e-12 * hi; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    (bound(mid) <= eps ? hi : lo) = mid;
+  }
+  return hi;
+}
 
 // The set-up of yq_set_particles (throws yq::Error).  The boundary data buffer
 // keeps its contents when the node count does not change.
@@ -658,6 +681,16 @@ void setup_particles(yq_problem* pb, int32_t n, const double* center_xy, const d
                     s);
 
   pb->fp = far_plan(N, N, 256, pb->far_want);
+  if (pb->prm.far_mode == YQ_FAR_CUTOFF) {
+    double L = 0.0;   // >= the total perimeter (each ellipse lies in its circle of radius A)
+    for (int i = 0; i < n; ++i) L += 2.0 * PI * pb->h_pc[5 * (size_t)i + 3];
+    const double eps = pb->prm.cutoff_tol;
+    pb->zcut64 = cutoff_z(kappa, L, eps, false);
+    pb->zcut64g = cutoff_z(kappa, L, eps, true);
+    pb->zcut32 = cutoff_z(kappa, L, std::max(eps, 0.1 * pb->prm.inner_tol), false);
+  } else {
+    pb->zcut64 = pb->zcut64g = pb->zcut32 = HUGE_VAL;
+  }
   if (use_fmm) {
     pb->fmm->use_mfma = pb->prm.fmm_m2l != YQ_M2L_VALU;
     pb->fmm->want_m2l32 = pb->prm.fmm_m2l == YQ_M2L_MFMA;

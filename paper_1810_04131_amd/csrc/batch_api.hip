@@ -91,6 +91,8 @@ int yq_batch_create(const yq_params* params, yq_batch** out) {
     int st = yq_create(params, &probe);  // validates the parameters
     YQ_REQUIRE(st == YQ_OK, st, std::string("bad parameters: ") + yq_last_error(nullptr));
     yq_destroy(probe);
+    YQ_REQUIRE(params->far_mode != YQ_FAR_CUTOFF, YQ_EINVAL,
+               "the cutoff far field is available to single problems only");
     auto b = std::make_unique<yq_batch>();
     b->prm = *params;
     b->eng.init(*params);

@@ -151,6 +151,10 @@ struct GeomView {
   const double4* ftile;  // bounding circles of 256-node source tiles
   const double4* fgrp;   // bounding circles of 64-node target groups
   const double4* fpan;   // bounding circles of 16-node panels
+  // cutoff far field: (group, tile) pairs with kappa x gap >= zcut are skipped in
+  // the value sums, >= zcut_g in the gradient sums (HUGE_VAL: exact sums)
+  double zcut = HUGE_VAL;
+  double zcut_g = HUGE_VAL;
 };
 
 // Discretisation constants, passed to kernels by value.
@@ -216,6 +220,7 @@ struct Far32View {
   double qc;           // sqrt(log2 e) / kappa: source strength scaling of the records
   float kap2;          // kappa^2 (general path)
   float nscale;        // kappa / sqrt(log2 e): general-path sum -> far-path scaling
+  double zcut = HUGE_VAL;  // tiles with kappa x gap >= zcut are skipped (cutoff far field)
 };
 
 void launch_far32_geom(const double* x, const double* y, int64_t N, double kappa, double4* tile,

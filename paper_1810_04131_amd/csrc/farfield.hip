@@ -40,6 +40,7 @@ FarPlan far_plan(int64_t nt, int64_t ns, int block, int want) {
 
 // stop (may be null): when *stop is set the launch does nothing (an operator
 // application that a converged GMRES no longer needs).
+template <bool CUT>
 __global__ __launch_bounds__(FAR_BS) void far64_kernel(GeomView g, const double* __restrict__ sigma,
                                                        int chunk, double* __restrict__ partial,
                                                        const int* __restrict__ stop) {
@@ -58,15 +59,30 @@ __global__ __launch_bounds__(FAR_BS) void far64_kernel(GeomView g, const double*
                       __builtin_amdgcn_readfirstlane((int)(threadIdx.x / FG));
   const bool live = grp * FG < N;
   double acc = 0.0;
+  // cutoff far field: a wavefront skips a tile whose pairs all lie beyond the
+  // cutoff (kappa x gap >= zc); a block skips staging a tile all its wavefronts skip
+  // (their flags are written before the first barrier and read after it)
+  __shared__ int wsk[FAR_BS / FG];
+  const double zc = g.zcut;
+  constexpr bool cut = CUT;   // zc < HUGE_VAL: the launchers pick the instantiation
+  bool wskip = false;
   for (int64_t jb = j0; jb < j1; jb += FAR_BS) {
+    if constexpr (cut) {
+      wskip = !live || far64_zmin(g.fgrp, g.ftile, grp, jb / FT, g.kappa) >= zc;
+      if (threadIdx.x % FG == 0) wsk[threadIdx.x / FG] = wskip;
+    }
     const int64_t j = jb + threadIdx.x;
     __syncthreads();
-    if (j < j1) {
+    bool bskip = cut;
+    if constexpr (cut)
+      for (int w = 0; w < FAR_BS / FG; ++w) bskip = bskip && wsk[w];
+    if (!bskip && j < j1) {
       const double s = sigma[j];
       sxy[threadIdx.x] = make_double2(g.x[j], g.y[j]);
       sq[threadIdx.x] = make_double2(g.wnx[j] * s, g.wny[j] * s);
     }
     __syncthreads();
+    if (wskip) continue;
     const int nb = (int)min((int64_t)FAR_BS, j1 - jb);
     // a tile with close pairs is summed panel by panel, each with its own class
     const int tcls = live ? far64_class(g.fgrp, g.ftile, grp, jb / FT, g.kappa) : C64_GENERAL;
@@ -159,6 +175,7 @@ __global__ void pack32_kernel(const float2* __restrict__ rel, const double* __re
 
 // Gradient far field: grad_x of the double layer,
 // (kappa^2/2pi) [ (K1(z)/z) q - ((x-y).q) (x-y) (K0(z) + 2 K1(z)/z) / r^2 ].
+template <bool CUT>
 __global__ __launch_bounds__(FAR_BS) void far_grad64_kernel(GeomView g,
                                                             const double* __restrict__ sigma,
                                                             int chunk,
@@ -176,15 +193,30 @@ __global__ __launch_bounds__(FAR_BS) void far_grad64_kernel(GeomView g,
                       __builtin_amdgcn_readfirstlane((int)(threadIdx.x / FG));
   const bool live = grp * FG < N;
   double ax = 0.0, ay = 0.0;
+  // cutoff far field: a wavefront skips a tile whose pairs all lie beyond the
+  // cutoff (kappa x gap >= zc); a block skips staging a tile all its wavefronts skip
+  // (their flags are written before the first barrier and read after it)
+  __shared__ int wsk[FAR_BS / FG];
+  const double zc = g.zcut_g;
+  constexpr bool cut = CUT;   // zc < HUGE_VAL: the launchers pick the instantiation
+  bool wskip = false;
   for (int64_t jb = j0; jb < j1; jb += FAR_BS) {
+    if constexpr (cut) {
+      wskip = !live || far64_zmin(g.fgrp, g.ftile, grp, jb / FT, g.kappa) >= zc;
+      if (threadIdx.x % FG == 0) wsk[threadIdx.x / FG] = wskip;
+    }
     const int64_t j = jb + threadIdx.x;
     __syncthreads();
-    if (j < j1) {
+    bool bskip = cut;
+    if constexpr (cut)
+      for (int w = 0; w < FAR_BS / FG; ++w) bskip = bskip && wsk[w];
+    if (!bskip && j < j1) {
       const double s = sigma[j];
       sxy[threadIdx.x] = make_double2(g.x[j], g.y[j]);
       sq[threadIdx.x] = make_double2(g.wnx[j] * s, g.wny[j] * s);
     }
     __syncthreads();
+    if (wskip) continue;
     const int nb = (int)min((int64_t)FAR_BS, j1 - jb);
     const int tcls = live ? far64_class(g.fgrp, g.ftile, grp, jb / FT, g.kappa) : C64_GENERAL;
     for (int q = 0; q < nb;) {   // as in far64_kernel
@@ -203,6 +235,7 @@ __global__ __launch_bounds__(FAR_BS) void far_grad64_kernel(GeomView g,
 
 // Far field and its gradient in one pass: partial[chunk * N + i] as far64_kernel,
 // gpartial[(chunk * 2 + c) * N + i] as far_grad64_kernel.
+template <bool CUT>
 __global__ __launch_bounds__(FAR_BS) void far_fused64_kernel(GeomView g,
                                                              const double* __restrict__ sigma,
                                                              int chunk,
@@ -221,15 +254,30 @@ __global__ __launch_bounds__(FAR_BS) void far_fused64_kernel(GeomView g,
                       __builtin_amdgcn_readfirstlane((int)(threadIdx.x / FG));
   const bool live = grp * FG < N;
   double acc = 0.0, ax = 0.0, ay = 0.0;
+  // cutoff far field: a wavefront skips a tile whose pairs all lie beyond the
+  // cutoff (kappa x gap >= zc); a block skips staging a tile all its wavefronts skip
+  // (their flags are written before the first barrier and read after it)
+  __shared__ int wsk[FAR_BS / FG];
+  const double zc = g.zcut_g;
+  constexpr bool cut = CUT;   // zc < HUGE_VAL: the launchers pick the instantiation
+  bool wskip = false;
   for (int64_t jb = j0; jb < j1; jb += FAR_BS) {
+    if constexpr (cut) {
+      wskip = !live || far64_zmin(g.fgrp, g.ftile, grp, jb / FT, g.kappa) >= zc;
+      if (threadIdx.x % FG == 0) wsk[threadIdx.x / FG] = wskip;
+    }
     const int64_t j = jb + threadIdx.x;
     __syncthreads();
-    if (j < j1) {
+    bool bskip = cut;
+    if constexpr (cut)
+      for (int w = 0; w < FAR_BS / FG; ++w) bskip = bskip && wsk[w];
+    if (!bskip && j < j1) {
       const double s = sigma[j];
       sxy[threadIdx.x] = make_double2(g.x[j], g.y[j]);
       sq[threadIdx.x] = make_double2(g.wnx[j] * s, g.wny[j] * s);
     }
     __syncthreads();
+    if (wskip) continue;
     const int nb = (int)min((int64_t)FAR_BS, j1 - jb);
     const int tcls = live ? far64_class(g.fgrp, g.ftile, grp, jb / FT, g.kappa) : C64_GENERAL;
     for (int q = 0; q < nb;) {   // as in far64_kernel
@@ -348,11 +396,12 @@ __global__ void finish_grad_kernel(GeomView g, int win, int chunks, const double
 void launch_far64(const GeomView& g, const double* sigma, const FarPlan& fp, double* partial,
                   hipStream_t s, const int* stop, hipEvent_t e0, hipEvent_t e1) {
   dim3 grid(fp.tblocks, fp.chunks);
+  auto k = g.zcut < HUGE_VAL ? far64_kernel<true> : far64_kernel<false>;
   if (e0)
-    hipExtLaunchKernelGGL(far64_kernel, grid, dim3(FAR_BS), 0, s, e0, e1, 0, g, sigma, fp.chunk,
-                          partial, stop);
+    hipExtLaunchKernelGGL(k, grid, dim3(FAR_BS), 0, s, e0, e1, 0, g, sigma, fp.chunk, partial,
+                          stop);
   else
-    far64_kernel<<<grid, FAR_BS, 0, s>>>(g, sigma, fp.chunk, partial, stop);
+    k<<<grid, FAR_BS, 0, s>>>(g, sigma, fp.chunk, partial, stop);
   YQ_HIP(hipGetLastError());
 }
 
@@ -388,14 +437,16 @@ void launch_far32(const Far32View& v, const FarPlan& fp, float* partial, hipStre
 void launch_far_fused64(const GeomView& g, const double* sigma, const FarPlan& fp,
                         double* partial, double* gpartial, hipStream_t s) {
   dim3 grid(fp.tblocks, fp.chunks);
-  far_fused64_kernel<<<grid, FAR_BS, 0, s>>>(g, sigma, fp.chunk, partial, gpartial);
+  auto k = g.zcut_g < HUGE_VAL ? far_fused64_kernel<true> : far_fused64_kernel<false>;
+  k<<<grid, FAR_BS, 0, s>>>(g, sigma, fp.chunk, partial, gpartial);
   YQ_HIP(hipGetLastError());
 }
 
 void launch_far_grad64(const GeomView& g, const double* sigma, const FarPlan& fp, double* partial,
                        hipStream_t s) {
   dim3 grid(fp.tblocks, fp.chunks);
-  far_grad64_kernel<<<grid, FAR_BS, 0, s>>>(g, sigma, fp.chunk, partial);
+  auto k = g.zcut_g < HUGE_VAL ? far_grad64_kernel<true> : far_grad64_kernel<false>;
+  k<<<grid, FAR_BS, 0, s>>>(g, sigma, fp.chunk, partial);
   YQ_HIP(hipGetLastError());
 }
 

@@ -192,6 +192,10 @@ __device__ __forceinline__ float far32_range(const Far32View& v, int64_t i, int6
     const int64_t te = min(j1, (t + 1) * FT);   // end of this tile within the range
     const double cx = gx - tcx, cy = gy - tcy;
     const double zt = v.kappa * (sqrt(cx * cx + cy * cy) - gr - tc[2]);
+    if (zt >= v.zcut) {   // cutoff far field: every pair of the tile is beyond the cutoff
+      jb = te;
+      continue;
+    }
     const float tx = (float)((xi - tcx) * v.s), ty = (float)((yi - tcy) * v.s);
     for (int64_t js = jb; js < te;) {
       double z;
@@ -221,12 +225,18 @@ __device__ __forceinline__ float far32_range(const Far32View& v, int64_t i, int6
   return fmaf(accn, v.nscale, accf);
 }
 
-__device__ __forceinline__ int far64_class(const double4* grp, const double4* tile, int64_t g,
-                                           int64_t t, double kappa) {
+// kappa x the gap between the bounding circles of target group g and source tile t
+__device__ __forceinline__ double far64_zmin(const double4* grp, const double4* tile, int64_t g,
+                                             int64_t t, double kappa) {
   kptr<double> gc = as_k((const double*)grp) + 4 * g;
   kptr<double> tc = as_k((const double*)tile) + 4 * t;
   const double cx = gc[0] - tc[0], cy = gc[1] - tc[1];
-  const double zmin = kappa * (sqrt(cx * cx + cy * cy) - gc[2] - tc[2]);
+  return kappa * (sqrt(cx * cx + cy * cy) - gc[2] - tc[2]);
+}
+
+__device__ __forceinline__ int far64_class(const double4* grp, const double4* tile, int64_t g,
+                                           int64_t t, double kappa) {
+  const double zmin = far64_zmin(grp, tile, g, t, kappa);
   return zmin >= 8.0 ? C64_Z8 : zmin >= 4.0 ? C64_Z4 : zmin >= 2.0 ? C64_Z2 : C64_GENERAL;
 }
 

@@ -24,6 +24,9 @@ struct yq_problem {
   std::unique_ptr<Fmm> fmm;     // far-field FMM (inner operator) when enabled
   std::unique_ptr<Fmm> fmm_hi;  // higher-order FP64 FMM for residuals (fmm_resid_order > 0)
   int far_want = 16384;       // far-field plan parameter (far_plan)
+  // cutoff far field: kappa x gap beyond which tile pairs are skipped, for the FP64
+  // value sums, the FP64 gradient sums and the FP32 sums (HUGE_VAL: exact sums)
+  double zcut64 = HUGE_VAL, zcut64g = HUGE_VAL, zcut32 = HUGE_VAL;
 
   std::vector<double> h_pc;  // [n*5]
   DevBuf<double> pc, x, y, nx, ny, w, wnx, wny, panel_h, pcx, pcy, pr;
@@ -112,6 +115,7 @@ struct yq_problem {
     v.qc = SQRT_LOG2E / kappa;   // the same expression as in pack32
     v.kap2 = (float)(kappa * kappa);
     v.nscale = (float)(kappa / SQRT_LOG2E);
+    v.zcut = zcut32;
     return v;
   }
 
@@ -139,6 +143,8 @@ struct yq_problem {
     g.ftile = ftile.p;
     g.fgrp = fgrp.p;
     g.fpan = fpan.p;
+    g.zcut = zcut64;
+    g.zcut_g = zcut64g;
     return g;
   }
 };

@@ -353,6 +353,8 @@ int yq_server_create(const yq_params* params, int64_t node_capacity, int32_t max
     int st = yq_create(params, &probe);
     YQ_REQUIRE(st == YQ_OK, st, std::string("bad parameters: ") + yq_last_error(nullptr));
     yq_destroy(probe);
+    YQ_REQUIRE(params->far_mode != YQ_FAR_CUTOFF, YQ_EINVAL,
+               "the cutoff far field is available to single problems only");
     auto s = std::make_unique<yq_server>();
     s->prm = *params;
     s->capacity = node_capacity;
