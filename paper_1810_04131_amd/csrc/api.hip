@@ -482,9 +482,14 @@ double cutoff_z(double kappa, double L, double eps, bool grad) {
 }
 
 // The set-up of yq_set_particles (throws yq::Error).  The boundary data buffer
-// keeps its contents when the node count does not change.
+// keeps its contents when the node count does not change.  rot (host [n] or null):
+// the particles are those of the current set-up moved rigidly, particle i turned
+// by rot[i].  The window part of the QBX correction only involves a particle's own
+// panels, and the kernel depends on distances and on normals relative to the
+// difference vector, so its values stay and its gradient rows turn with the
+// particle: the QBX build is replaced by that rotation.
 void setup_particles(yq_problem* pb, int32_t n, const double* center_xy, const double* angle,
-                     const double* semi_axes, double kappa) {
+                     const double* semi_axes, double kappa, const double* rot = nullptr) {
   YQ_REQUIRE(pb && center_xy && angle && semi_axes, YQ_EINVAL, "null argument");
   YQ_REQUIRE(n >= 1, YQ_EINVAL, "need at least one particle");
   YQ_REQUIRE(std::isfinite(kappa) && kappa > 0.0, YQ_EINVAL, "kappa must be finite and > 0");
@@ -511,6 +516,8 @@ void setup_particles(yq_problem* pb, int32_t n, const double* center_xy, const d
   pb->ready = false;
   pb->pot_fine_ready = false;
   pb->have_f = false;
+  const bool had_qbx = pb->qbx_valid;   // W, WGx, WGy hold the current set-up's correction
+  pb->qbx_valid = false;
   pb->n = n;
   pb->N = N;
   pb->kappa = kappa;
@@ -650,10 +657,25 @@ void setup_particles(yq_problem* pb, int32_t n, const double* center_xy, const d
     pb->interp_ready = true;
   }
   const size_t wsz = (size_t)(2 * pb->prm.qbx_window + 1) * Q * N;
+  const bool reuse = rot && had_qbx && pb->W.p && pb->W.n == wsz;
   pb->W.alloc(wsz);
   pb->WGx.alloc(wsz);
   pb->WGy.alloc(wsz);
-  {
+  if (reuse) {
+    Timed t(pb, 4);
+    pb->wrot.fit((size_t)2 * n);
+    pb->rstage.fit((size_t)2 * n * sizeof(double));
+    double* cs = (double*)pb->rstage.p;
+    for (int i = 0; i < n; ++i) {
+      cs[2 * i] = std::cos(rot[i]);
+      cs[2 * i + 1] = std::sin(rot[i]);
+    }
+    YQ_HIP(hipMemcpyAsync(pb->wrot.p, cs, 2 * (size_t)n * sizeof(double), hipMemcpyHostToDevice, s));
+    // (the next set-up writes rstage only after its geometry check has synchronised
+    // the stream, so this copy has completed by then)
+    launch_rotate_grad_rows(pb->WGx.p, pb->WGy.p, (int64_t)(2 * pb->prm.qbx_window + 1) * Q, N,
+                            (int64_t)P * Q, pb->wrot.p, s);
+  } else {
     Timed t(pb, 4);
     const int qs = pb->prm.qbx_oversample;
     const size_t nq = (size_t)N * qs;
@@ -667,6 +689,7 @@ void setup_particles(yq_problem* pb, int32_t n, const double* center_xy, const d
                      pb->Lqbx.p, pb->qfx.p, pb->qfy.p, pb->qfwx.p, pb->qfwy.p, pb->W.p,
                      pb->WGx.p, pb->WGy.p, s);
   }
+  pb->qbx_valid = true;
   if (pb->x_total > 0)
     launch_near_rows(g, pb->consts, pb->prm.near_oversample, pb->Lnear.p, pb->xrow.p,
                      pb->xpan.p, pb->xvals.p, pb->xgvals.p, s);
@@ -1210,8 +1233,10 @@ int yq_step(yq_problem* pb, const yq_dynamics* dyn, double* sigma, double* sigma
       oang[i] = o[2];
     }
     const double kappa = pb->kappa;
+    std::vector<double> rot(n);
+    for (int i = 0; i < n; ++i) rot[i] = ang[i] - oang[i];
     try {
-      setup_particles(pb, n, cxy.data(), ang.data(), ax.data(), kappa);
+      setup_particles(pb, n, cxy.data(), ang.data(), ax.data(), kappa, rot.data());
     } catch (const Error& e) {
       if (e.code != YQ_EGEOM) throw;
       // rejected: rebuild the configuration the step started from

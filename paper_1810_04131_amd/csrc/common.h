@@ -301,6 +301,10 @@ struct DynArgs {
 };
 void launch_circles3(const double* pc, int n, double4* cc, double* rad, hipStream_t s);
 void launch_repulsion(const DynArgs& a, hipStream_t s);
+// (gx, gy) <- R (gx, gy) for entries k * N + i (k < K), R the turn of node i's
+// particle (i / npp): cs [2n] holds its (cos, sin)
+void launch_rotate_grad_rows(double* gx, double* gy, int64_t K, int64_t N, int64_t npp,
+                             const double* cs, hipStream_t s);
 // sigma <- 2 sigma - sigma_prev, sigma_prev <- the old sigma
 void launch_predict(double* sigma, double* sigma_prev, int64_t N, hipStream_t s);
 

@@ -123,7 +123,31 @@ __global__ __launch_bounds__(DB) void predict_kernel(double* __restrict__ s, dou
   p[i] = si;
 }
 
+// The gradient rows of the window QBX correction turned with their particle.
+__global__ __launch_bounds__(DB) void rotate_grad_rows_kernel(double* __restrict__ gx,
+                                                              double* __restrict__ gy, int64_t N,
+                                                              int64_t npp,
+                                                              const double* __restrict__ cs) {
+  const int64_t i = (int64_t)blockIdx.x * DB + threadIdx.x;
+  if (i >= N) return;
+  const int64_t o = (int64_t)blockIdx.y * N + i;
+  const int64_t p = i / npp;
+  const double c = cs[2 * p], s = cs[2 * p + 1];
+  const double a = gx[o], b = gy[o];
+  gx[o] = c * a - s * b;
+  gy[o] = s * a + c * b;
+}
+
 }  // namespace
+
+void launch_rotate_grad_rows(double* gx, double* gy, int64_t K, int64_t N, int64_t npp,
+                             const double* cs, hipStream_t s) {
+  if (N <= 0 || K <= 0) return;
+  YQ_REQUIRE(K <= 65535 && npp > 0 && N % npp == 0, YQ_EINVAL, "rotate_grad_rows: bad shape");
+  rotate_grad_rows_kernel<<<dim3((unsigned)((N + DB - 1) / DB), (unsigned)K), DB, 0, s>>>(
+      gx, gy, N, npp, cs);
+  YQ_HIP(hipGetLastError());
+}
 
 void launch_predict(double* sigma, double* sigma_prev, int64_t N, hipStream_t s) {
   if (N <= 0) return;

@@ -57,6 +57,9 @@ struct yq_problem {
   PinnedBuf hflags;  // set-up: geometry check flag and near-panel total
   DevBuf<char> scan_tmp;
   bool interp_ready = false;   // Lqbx, Lnear, Lpot uploaded
+  bool qbx_valid = false;      // W, WGx, WGy hold the current set-up's window correction
+  DevBuf<double> wrot;         // per particle (cos, sin) of a rigid turn (time stepping)
+  PinnedBuf rstage;
   // device-side Arnoldi bookkeeping (H, rotations, g, 1 / h_{j+1,j}, step status)
   DevBuf<double> gm;
   DevBuf<int> gstop;            // set when the GMRES cycle has stopped

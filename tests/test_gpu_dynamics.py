@@ -177,6 +177,34 @@ def test_extrapolated_guess_is_two_sigma_minus_prev():
         pb.step(sigma, dt=0.1, xi_x=1.0, xi_theta=1.0, c0=0.02, sigma_prev=sigma)
 
 
+def test_step_turns_the_window_correction_with_the_particles():
+    # A step replaces the QBX build by turning the gradient rows of the window
+    # correction with each particle; the operator and the surface gradient then
+    # agree with a fresh set-up at the new configuration to rounding.  Both sides
+    # build from absolute node coordinates (|x| ~ 14 here), whose 1e-16 relative
+    # rounding becomes ~1e-13 in the differences of adjacent nodes, so the bounds are
+    # the FP64 parity's: 1e-12 for the operator, 1e-11 for the gradient (its
+    # near-singular rows cancel more).  A missing turn would be off by ~1e-1.
+    torch = _torch()
+    parts = workloads.random_ellipses(8, 14.0, 1.0, seed=6, gap=0.4)
+    pb = _problem(parts, 16, 8, tol=1e-12)
+    pb.set_boundary_data(pb.boundary_label())
+    sigma = torch.zeros(pb.N, dtype=torch.float64, device=pb.device)
+    for _ in range(2):
+        pb.step(sigma, dt=0.3, xi_x=1.0, xi_theta=0.5, c0=0.02)
+    c, a = pb.particles()
+    assert np.abs(a - parts.angle).max() > 1e-3
+    moved = parts.copy()
+    moved.center, moved.angle = c, a
+    fresh = _problem(moved, 16, 8, tol=1e-12)
+    v = workloads.random_density(pb.N, 9)
+    assert _rel(_np(pb.apply_operator(v)), _np(fresh.apply_operator(v))) < 1e-12
+    g1, g2 = pb.surface_gradient(v), fresh.surface_gradient(v)
+    scale = max(np.abs(_np(g2[0])).max(), np.abs(_np(g2[1])).max())
+    for u, w in zip(g1, g2):
+        assert np.abs(_np(u) - _np(w)).max() < 1e-11 * scale
+
+
 def test_rejected_configuration_leaves_particles_in_place():
     # Hydrophobic heads facing each other 0.3 apart attract along the line of
     # centres; a dt that moves each particle by 1.5 gaps overlaps them.
