@@ -112,6 +112,25 @@ def test_cutoff_solve_and_forces_match_the_oracle(precision):
     assert abs(E - Eo) < 1e-9 * abs(Eo)
 
 
+def test_cutoff_at_the_large_workload_size():
+    # The 500-ellipse workload (N = 256,000) at kappa 4, where the cutoff skips
+    # all but a few percent of the tile pairs: 48 sampled rows against the
+    # oracle's exact sums, within the bound.
+    parts = workloads.config_large(seed=0)["particles"].copy()
+    parts.kappa = 4.0
+    pb = _problem(parts, 32, 10, far_mode=yq.YQ_FAR_CUTOFF, cutoff_tol=1e-12)
+    d = oracle.discretize(parts, Params(panels=32, qbx_order=10))
+    assert pb.N == d.N == 256000
+    sig = workloads.random_density(d.N, 31)
+    rows = np.linspace(0, d.N - 1, 48).astype(int)
+    ref = oracle.far_rows(d, list(rows), sig)
+    smax = np.abs(sig).max()
+    got = _np(pb.apply_far(sig))[rows]
+    assert np.abs(got - ref).max() <= 1e-12 * smax + 1e-12 * np.abs(ref).max()
+    got32 = _np(pb.apply_far(sig, precision=yq.YQ_MIXED))[rows]
+    assert np.abs(got32 - ref).max() <= 1e-7 * smax + 5e-6 * np.abs(ref).max()
+
+
 def test_cutoff_parameters_and_batches():
     _torch()
     with pytest.raises(yq.YQError):
