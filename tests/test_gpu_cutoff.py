@@ -131,6 +131,29 @@ def test_cutoff_at_the_large_workload_size():
     assert np.abs(got32 - ref).max() <= 1e-7 * smax + 5e-6 * np.abs(ref).max()
 
 
+def test_time_steps_with_the_cutoff_match_the_direct_sum():
+    # Two constant-drag steps of 12 ellipses at kappa 2: with the cutoff the
+    # forces and the new positions agree with the exact direct sums to the solve
+    # tolerance.
+    torch = _torch()
+    parts = workloads.random_ellipses(12, 24.0, 2.0, seed=5, gap=0.4)
+    dyn = dict(dt=0.05, xi_x=1.5, xi_theta=2.0, c0=0.02)
+    out = []
+    for mode in (yq.YQ_FAR_DIRECT, yq.YQ_FAR_CUTOFF):
+        pb = _problem(parts, 16, 8, tol=1e-10, precision=yq.YQ_MIXED, far_mode=mode,
+                      cutoff_tol=1e-12)
+        pb.set_boundary_data(pb.boundary_label())
+        sigma = torch.zeros(pb.N, dtype=torch.float64, device=pb.device)
+        for _ in range(2):
+            info, F, T, E = pb.step(sigma, **dyn)
+        out.append((pb.particles(), _np(F), _np(T)))
+    (c0, a0), F0, T0 = out[0]
+    (c1, a1), F1, T1 = out[1]
+    assert np.abs(F1 - F0).max() < 1e-8 * np.abs(F0).max()
+    assert np.abs(T1 - T0).max() < 1e-8 * max(np.abs(F0).max(), np.abs(T0).max())
+    assert np.abs(c1 - c0).max() < 1e-10 and np.abs(a1 - a0).max() < 1e-10
+
+
 def test_cutoff_parameters_and_batches():
     _torch()
     with pytest.raises(yq.YQError):
