@@ -607,57 +607,73 @@ __global__ void l2l_kernel(int p, int nbox, const int* __restrict__ parent, cons
   Lc[t] = sum;
 }
 
+// Waves per leaf in l2p_p2p_kernel: wave w takes every PW-th neighbour leaf of the
+// 3 x 3 neighbourhood (a leaf holds at most 64 targets, so one wave per leaf left most
+// SIMDs with a single wave to hide latency); the waves' partial sums are combined in
+// a fixed order by wave 0, which also evaluates the local expansion.
+constexpr int PW = 4;
+
+// Orders this wave's LDS writes before its later reads (wave-local exchange).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // One block per leaf: local expansion at the leaf's targets plus the direct
 // interactions with the 3 x 3 neighbourhood; writes partial[node] in the far-field
 // kernels' scaling (far field * 2 pi / kappa^2).
 template <bool F32>
-__global__ __launch_bounds__(FB) void l2p_p2p_kernel(int p, double kappa, int use_local, int use_col,
-                                                     const int* __restrict__ ls,
-                                                     const int* __restrict__ lc,
-                                                     const int* __restrict__ nbp,
-                                                     const int* __restrict__ nbi,
-                                                     const double* __restrict__ ccx,
-                                                     const double* __restrict__ ccy,
-                                                     const double2* __restrict__ L,
-                                                     const double* __restrict__ xs,
-                                                     const double* __restrict__ ys,
-                                                     const double* __restrict__ qx,
-                                                     const double* __restrict__ qy,
-                                                     const int* __restrict__ perm,
-                                                     const double* __restrict__ tab,
-                                                     double* __restrict__ partial,
-                                                     const int* __restrict__ stop) {
+__global__ __launch_bounds__(FB * PW) void l2p_p2p_kernel(int p, double kappa, int use_local, int use_col,
+                                                          const int* __restrict__ ls,
+                                                          const int* __restrict__ lc,
+                                                          const int* __restrict__ nbp,
+                                                          const int* __restrict__ nbi,
+                                                          const double* __restrict__ ccx,
+                                                          const double* __restrict__ ccy,
+                                                          const double2* __restrict__ L,
+                                                          const double* __restrict__ xs,
+                                                          const double* __restrict__ ys,
+                                                          const double* __restrict__ qx,
+                                                          const double* __restrict__ qy,
+                                                          const int* __restrict__ perm,
+                                                          const double* __restrict__ tab,
+                                                          double* __restrict__ partial,
+                                                          const int* __restrict__ stop) {
   if (stop && *stop) return;
   extern __shared__ double sh[];
-  double2* sxy = reinterpret_cast<double2*>(sh);            // [FB]
-  double2* sq = sxy + FB;                                   // [FB] (FP64 strengths)
-  float2* sq32 = reinterpret_cast<float2*>(sq + FB);        // [FB] (FP32 strengths)
-  double* col = reinterpret_cast<double*>(sq32 + FB) + threadIdx.x;   // [(p + 1) * 64] scaled I_n
-  const int tid = threadIdx.x;
+  const int lane = threadIdx.x % FB, w = threadIdx.x / FB;
+  double2* sbase = reinterpret_cast<double2*>(sh);
+  double2* sxy = sbase + w * FB;                                        // [PW][FB]
+  double2* sq = sbase + (PW + w) * FB;                                  // [PW][FB] (FP64)
+  float2* sq32 = reinterpret_cast<float2*>(sbase + 2 * PW * FB) + w * FB;   // [PW][FB] (FP32)
+  double* red = reinterpret_cast<double*>(reinterpret_cast<float2*>(sbase + 2 * PW * FB) +
+                                          PW * FB);                     // [PW][FB] wave sums
+  double* col = red + PW * FB + lane;   // [(p + 1) * 64] scaled I_n, wave 0
   const int b = blockIdx.x;
   const int s0 = ls[b], cnt = lc[b];
   const double kap2 = kappa * kappa;
   const double cx = ccx[b], cy = ccy[b];
   for (int r0 = 0; r0 < cnt; r0 += FB) {
-    const int j = r0 + tid;
+    const int j = r0 + lane;
     const bool act = j < cnt;
     const double xi = act ? xs[s0 + j] : cx, yi = act ? ys[s0 + j] : cy;
     double acc64 = 0.0;
     float acc32 = 0.0f;
-    for (int e = nbp[b]; e < nbp[b + 1]; ++e) {
+    for (int e = nbp[b] + w; e < nbp[b + 1]; e += PW) {
       const int nb = nbi[e];
       const int t0 = ls[nb], tc = lc[nb];
       for (int k0 = 0; k0 < tc; k0 += FB) {
-        __syncthreads();
-        if (k0 + tid < tc) {
-          const int k = t0 + k0 + tid;
-          sxy[tid] = make_double2(xs[k], ys[k]);
+        wave_sync();   // this wave's reads of the previous tile are done
+        if (k0 + lane < tc) {
+          const int k = t0 + k0 + lane;
+          sxy[lane] = make_double2(xs[k], ys[k]);
           if (F32)
-            sq32[tid] = make_float2((float)qx[k], (float)qy[k]);
+            sq32[lane] = make_float2((float)qx[k], (float)qy[k]);
           else
-            sq[tid] = make_double2(qx[k], qy[k]);
+            sq[lane] = make_double2(qx[k], qy[k]);
         }
-        __syncthreads();
+        wave_sync();
         const int nbk = min(FB, tc - k0);
         if (F32)
           acc32 = far32_tile(xi, yi, sxy, sq32, nbk, (float)kap2, acc32);
@@ -665,28 +681,32 @@ __global__ __launch_bounds__(FB) void l2p_p2p_kernel(int p, double kappa, int us
           acc64 = far64_tile(xi, yi, sxy, sq, nbk, kap2, tab, acc64);
       }
     }
-    double loc = 0.0;
-    if (use_local && act) {
-      const double dx = xi - cx, dy = yi - cy;
-      const double rho = sqrt(dx * dx + dy * dy);
-      const double x = kappa * rho, t = 0.25 * x * x, hx = 0.5 * x;
-      const double2 e1 = rho > 0.0 ? make_double2(dx / rho, dy / rho) : make_double2(1.0, 0.0);
-      const double2* lb = L + (int64_t)b * (p + 1);
-      if (use_col) iscaled_col(t, p, col);
-      loc = lb[0].x * (use_col ? col[0] : iorder(t, 1.0, 0));
-      double2 E = e1;
-      double pref = 1.0;                      // (x/2)^n / n!
-      for (int n = 1; n <= p; ++n) {
-        pref *= hx * rcp64(double(n));
-        const double2 v = cmul(lb[n], E);
-        loc += 2.0 * v.x * (use_col ? pref * col[n * 64] : iorder(t, pref, n));
-        E = cmul(E, e1);
+    red[w * FB + lane] = F32 ? (double)acc32 : acc64;
+    __syncthreads();
+    if (w == 0) {
+      double direct = red[lane];
+      for (int q = 1; q < PW; ++q) direct += red[q * FB + lane];
+      double loc = 0.0;
+      if (use_local && act) {
+        const double dx = xi - cx, dy = yi - cy;
+        const double rho = sqrt(dx * dx + dy * dy);
+        const double x = kappa * rho, t = 0.25 * x * x, hx = 0.5 * x;
+        const double2 e1 = rho > 0.0 ? make_double2(dx / rho, dy / rho) : make_double2(1.0, 0.0);
+        const double2* lb = L + (int64_t)b * (p + 1);
+        if (use_col) iscaled_col(t, p, col);
+        loc = lb[0].x * (use_col ? col[0] : iorder(t, 1.0, 0));
+        double2 E = e1;
+        double pref = 1.0;                      // (x/2)^n / n!
+        for (int n = 1; n <= p; ++n) {
+          pref *= hx * rcp64(double(n));
+          const double2 v = cmul(lb[n], E);
+          loc += 2.0 * v.x * (use_col ? pref * col[n * 64] : iorder(t, pref, n));
+          E = cmul(E, e1);
+        }
       }
+      if (act) partial[perm[s0 + j]] = direct + loc * (2.0 * PI / kap2);
     }
-    if (act) {
-      const double direct = F32 ? (double)acc32 : acc64;
-      partial[perm[s0 + j]] = direct + loc * (2.0 * PI / kap2);
-    }
+    __syncthreads();   // red is rewritten by the next group of targets
   }
 }
 
@@ -1422,16 +1442,18 @@ void Fmm::apply(const double* sigma, double* partial, bool p2p_fp32, const doubl
   expansions(sigma, s, p2p_fp32 && want_m2l32 && use_mfma, stop);
   FmmLevel& leaf = lv[depth];
   const int col = p <= kColMaxOrder;
-  const size_t sh_l = (size_t)FB * (2 * sizeof(double2) + sizeof(float2)) +
+  const size_t sh_l = (size_t)PW * FB * (2 * sizeof(double2) + sizeof(float2) + sizeof(double)) +
                       (col ? (size_t)(p + 1) * 64 * sizeof(double) : 0);
   if (p2p_fp32)
-    l2p_p2p_kernel<true><<<leaf.nbox, FB, sh_l, s>>>(p, kappa, 1, col, leaf_start.p, leaf_cnt.p, nbp.p,
-                                                     nbi.p, leaf.cx.p, leaf.cy.p, leaf.L.p, xs.p, ys.p,
-                                                     qx.p, qy.p, perm.p, tab, partial, stop);
+    l2p_p2p_kernel<true><<<leaf.nbox, FB * PW, sh_l, s>>>(p, kappa, 1, col, leaf_start.p, leaf_cnt.p,
+                                                          nbp.p, nbi.p, leaf.cx.p, leaf.cy.p, leaf.L.p,
+                                                          xs.p, ys.p, qx.p, qy.p, perm.p, tab, partial,
+                                                          stop);
   else
-    l2p_p2p_kernel<false><<<leaf.nbox, FB, sh_l, s>>>(p, kappa, 1, col, leaf_start.p, leaf_cnt.p, nbp.p,
-                                                      nbi.p, leaf.cx.p, leaf.cy.p, leaf.L.p, xs.p,
-                                                      ys.p, qx.p, qy.p, perm.p, tab, partial, stop);
+    l2p_p2p_kernel<false><<<leaf.nbox, FB * PW, sh_l, s>>>(p, kappa, 1, col, leaf_start.p, leaf_cnt.p,
+                                                           nbp.p, nbi.p, leaf.cx.p, leaf.cy.p, leaf.L.p,
+                                                           xs.p, ys.p, qx.p, qy.p, perm.p, tab, partial,
+                                                           stop);
   YQ_HIP(hipGetLastError());
 }
 
