@@ -717,7 +717,7 @@ __global__ __launch_bounds__(FB * PW) void l2p_p2p_kernel(int p, double kappa, i
 // since (d/dx + i d/dy) I_n(kappa rho) e^{i n theta} = kappa I_{n+1} e^{i(n+1) theta} for
 // every integer n (I_{-n} = I_n).  Writes gpart[node] (x) and gpart[N + node] (y) in
 // the gradient far-field kernels' scaling.
-__global__ __launch_bounds__(FB) void l2p_p2p_grad_kernel(int p, int use_col, double kappa,
+__global__ __launch_bounds__(FB * PW) void l2p_p2p_grad_kernel(int p, int use_col, double kappa,
                                                           const int* __restrict__ ls,
                                                           const int* __restrict__ lc,
                                                           const int* __restrict__ nbp,
@@ -732,35 +732,46 @@ __global__ __launch_bounds__(FB) void l2p_p2p_grad_kernel(int p, int use_col, do
                                                           const int* __restrict__ perm, int64_t N,
                                                           const double* __restrict__ tab,
                                                           double* __restrict__ gpart) {
+  // the neighbour leaves are split over PW wavefronts as in l2p_p2p_kernel
   extern __shared__ double sh[];
-  double2* sxy = reinterpret_cast<double2*>(sh);            // [FB]
-  double2* sq = sxy + FB;                                   // [FB]
-  double* col = reinterpret_cast<double*>(sq + FB) + threadIdx.x;   // [(p + 2) * 64] scaled I_n
-  const int tid = threadIdx.x;
+  const int lane = threadIdx.x % FB, w = threadIdx.x / FB;
+  double2* sbase = reinterpret_cast<double2*>(sh);
+  double2* sxy = sbase + w * FB;                              // [PW][FB]
+  double2* sq = sbase + (PW + w) * FB;                        // [PW][FB]
+  double2* red = sbase + 2 * PW * FB;                         // [PW][FB] wave sums (x, y)
+  double* col = reinterpret_cast<double*>(red + PW * FB) + lane;   // [(p + 2) * 64] scaled I_n
   const int b = blockIdx.x;
   const int s0 = ls[b], cnt = lc[b];
   const double kap2 = kappa * kappa;
   const double cx = ccx[b], cy = ccy[b];
   for (int r0 = 0; r0 < cnt; r0 += FB) {
-    const int j = r0 + tid;
+    const int j = r0 + lane;
     const bool act = j < cnt;
     const double xi = act ? xs[s0 + j] : cx, yi = act ? ys[s0 + j] : cy;
     double ax = 0.0, ay = 0.0;
-    for (int e = nbp[b]; e < nbp[b + 1]; ++e) {
+    for (int e = nbp[b] + w; e < nbp[b + 1]; e += PW) {
       const int nb = nbi[e];
       const int t0 = ls[nb], tc = lc[nb];
       for (int k0 = 0; k0 < tc; k0 += FB) {
-        __syncthreads();
-        if (k0 + tid < tc) {
-          const int k = t0 + k0 + tid;
-          sxy[tid] = make_double2(xs[k], ys[k]);
-          sq[tid] = make_double2(qx[k], qy[k]);
+        wave_sync();   // this wave's reads of the previous tile are done
+        if (k0 + lane < tc) {
+          const int k = t0 + k0 + lane;
+          sxy[lane] = make_double2(xs[k], ys[k]);
+          sq[lane] = make_double2(qx[k], qy[k]);
         }
-        __syncthreads();
+        wave_sync();
         far_grad64_tile(xi, yi, sxy, sq, min(FB, tc - k0), kap2, tab, ax, ay);
       }
     }
-    if (act) {
+    red[w * FB + lane] = make_double2(ax, ay);
+    __syncthreads();
+    if (w == 0) {
+      for (int q = 1; q < PW; ++q) {
+        ax += red[q * FB + lane].x;
+        ay += red[q * FB + lane].y;
+      }
+    }
+    if (w == 0 && act) {
       const double dx = xi - cx, dy = yi - cy;
       const double rho = sqrt(dx * dx + dy * dy);
       const double x = kappa * rho, t = 0.25 * x * x, hx = 0.5 * x;
@@ -790,6 +801,7 @@ __global__ __launch_bounds__(FB) void l2p_p2p_grad_kernel(int p, int use_col, do
       gpart[node] = ax + G.x * sc;
       gpart[N + node] = ay + G.y * sc;
     }
+    __syncthreads();   // red is rewritten by the next group of targets
   }
 }
 
@@ -1462,10 +1474,10 @@ void Fmm::apply_grad(const double* sigma, double* gpart, const double* tab, hipS
   FmmLevel& leaf = lv[depth];
   const int col = p <= kColMaxOrder;
   const size_t sh =
-      (size_t)FB * 2 * sizeof(double2) + (col ? (size_t)(p + 2) * 64 * sizeof(double) : 0);
-  l2p_p2p_grad_kernel<<<leaf.nbox, FB, sh, s>>>(p, col, kappa, leaf_start.p, leaf_cnt.p, nbp.p, nbi.p,
-                                                 leaf.cx.p, leaf.cy.p, leaf.L.p, xs.p, ys.p, qx.p,
-                                                 qy.p, perm.p, N, tab, gpart);
+      (size_t)PW * FB * 3 * sizeof(double2) + (col ? (size_t)(p + 2) * 64 * sizeof(double) : 0);
+  l2p_p2p_grad_kernel<<<leaf.nbox, FB * PW, sh, s>>>(p, col, kappa, leaf_start.p, leaf_cnt.p, nbp.p,
+                                                      nbi.p, leaf.cx.p, leaf.cy.p, leaf.L.p, xs.p,
+                                                      ys.p, qx.p, qy.p, perm.p, N, tab, gpart);
   YQ_HIP(hipGetLastError());
 }
 
