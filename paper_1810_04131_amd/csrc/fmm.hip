@@ -607,11 +607,15 @@ __global__ void l2l_kernel(int p, int nbox, const int* __restrict__ parent, cons
   Lc[t] = sum;
 }
 
-// Waves per leaf in l2p_p2p_kernel: wave w takes every PW-th neighbour leaf of the
-// 3 x 3 neighbourhood (a leaf holds at most 64 targets, so one wave per leaf left most
-// SIMDs with a single wave to hide latency); the waves' partial sums are combined in
-// a fixed order by wave 0, which also evaluates the local expansion.
+// Waves per leaf in l2p_p2p_grad_kernel (and l2p_p2p_kernel below kLeavesFor2): wave
+// w takes every PW-th neighbour leaf of the 3 x 3 neighbourhood (a leaf holds at most
+// 64 targets, so one wave per leaf left most SIMDs with a single wave to hide latency);
+// the waves' partial sums are combined in a fixed order by wave 0, which also
+// evaluates the local expansion.  From kLeavesFor2 leaves on the leaves alone fill the
+// SIMDs and l2p_p2p_kernel takes two waves per leaf (measured: 4 waves best at 800
+// leaves, 2 at 4,000; 8 slower at both).
 constexpr int PW = 4;
+constexpr int kLeavesFor2 = 2048;
 
 // Orders this wave's LDS writes before its later reads (wave-local exchange).
 __device__ __forceinline__ void wave_sync() {
@@ -623,8 +627,8 @@ __device__ __forceinline__ void wave_sync() {
 // One block per leaf: local expansion at the leaf's targets plus the direct
 // interactions with the 3 x 3 neighbourhood; writes partial[node] in the far-field
 // kernels' scaling (far field * 2 pi / kappa^2).
-template <bool F32>
-__global__ __launch_bounds__(FB * PW) void l2p_p2p_kernel(int p, double kappa, int use_local, int use_col,
+template <bool F32, int NW>
+__global__ __launch_bounds__(FB * NW) void l2p_p2p_kernel(int p, double kappa, int use_local, int use_col,
                                                           const int* __restrict__ ls,
                                                           const int* __restrict__ lc,
                                                           const int* __restrict__ nbp,
@@ -644,12 +648,12 @@ __global__ __launch_bounds__(FB * PW) void l2p_p2p_kernel(int p, double kappa, i
   extern __shared__ double sh[];
   const int lane = threadIdx.x % FB, w = threadIdx.x / FB;
   double2* sbase = reinterpret_cast<double2*>(sh);
-  double2* sxy = sbase + w * FB;                                        // [PW][FB]
-  double2* sq = sbase + (PW + w) * FB;                                  // [PW][FB] (FP64)
-  float2* sq32 = reinterpret_cast<float2*>(sbase + 2 * PW * FB) + w * FB;   // [PW][FB] (FP32)
-  double* red = reinterpret_cast<double*>(reinterpret_cast<float2*>(sbase + 2 * PW * FB) +
-                                          PW * FB);                     // [PW][FB] wave sums
-  double* col = red + PW * FB + lane;   // [(p + 1) * 64] scaled I_n, wave 0
+  double2* sxy = sbase + w * FB;                                        // [NW][FB]
+  double2* sq = sbase + (NW + w) * FB;                                  // [NW][FB] (FP64)
+  float2* sq32 = reinterpret_cast<float2*>(sbase + 2 * NW * FB) + w * FB;   // [NW][FB] (FP32)
+  double* red = reinterpret_cast<double*>(reinterpret_cast<float2*>(sbase + 2 * NW * FB) +
+                                          NW * FB);                     // [NW][FB] wave sums
+  double* col = red + NW * FB + lane;   // [(p + 1) * 64] scaled I_n, wave 0
   const int b = blockIdx.x;
   const int s0 = ls[b], cnt = lc[b];
   const double kap2 = kappa * kappa;
@@ -660,7 +664,7 @@ __global__ __launch_bounds__(FB * PW) void l2p_p2p_kernel(int p, double kappa, i
     const double xi = act ? xs[s0 + j] : cx, yi = act ? ys[s0 + j] : cy;
     double acc64 = 0.0;
     float acc32 = 0.0f;
-    for (int e = nbp[b] + w; e < nbp[b + 1]; e += PW) {
+    for (int e = nbp[b] + w; e < nbp[b + 1]; e += NW) {
       const int nb = nbi[e];
       const int t0 = ls[nb], tc = lc[nb];
       for (int k0 = 0; k0 < tc; k0 += FB) {
@@ -685,7 +689,7 @@ __global__ __launch_bounds__(FB * PW) void l2p_p2p_kernel(int p, double kappa, i
     __syncthreads();
     if (w == 0) {
       double direct = red[lane];
-      for (int q = 1; q < PW; ++q) direct += red[q * FB + lane];
+      for (int q = 1; q < NW; ++q) direct += red[q * FB + lane];
       double loc = 0.0;
       if (use_local && act) {
         const double dx = xi - cx, dy = yi - cy;
@@ -1454,18 +1458,14 @@ void Fmm::apply(const double* sigma, double* partial, bool p2p_fp32, const doubl
   expansions(sigma, s, p2p_fp32 && want_m2l32 && use_mfma, stop);
   FmmLevel& leaf = lv[depth];
   const int col = p <= kColMaxOrder;
-  const size_t sh_l = (size_t)PW * FB * (2 * sizeof(double2) + sizeof(float2) + sizeof(double)) +
+  const int nw = leaf.nbox >= kLeavesFor2 ? 2 : PW;
+  const size_t sh_l = (size_t)nw * FB * (2 * sizeof(double2) + sizeof(float2) + sizeof(double)) +
                       (col ? (size_t)(p + 1) * 64 * sizeof(double) : 0);
-  if (p2p_fp32)
-    l2p_p2p_kernel<true><<<leaf.nbox, FB * PW, sh_l, s>>>(p, kappa, 1, col, leaf_start.p, leaf_cnt.p,
-                                                          nbp.p, nbi.p, leaf.cx.p, leaf.cy.p, leaf.L.p,
-                                                          xs.p, ys.p, qx.p, qy.p, perm.p, tab, partial,
-                                                          stop);
-  else
-    l2p_p2p_kernel<false><<<leaf.nbox, FB * PW, sh_l, s>>>(p, kappa, 1, col, leaf_start.p, leaf_cnt.p,
-                                                           nbp.p, nbi.p, leaf.cx.p, leaf.cy.p, leaf.L.p,
-                                                           xs.p, ys.p, qx.p, qy.p, perm.p, tab, partial,
-                                                           stop);
+  auto k = p2p_fp32 ? (nw == 2 ? l2p_p2p_kernel<true, 2> : l2p_p2p_kernel<true, PW>)
+                    : (nw == 2 ? l2p_p2p_kernel<false, 2> : l2p_p2p_kernel<false, PW>);
+  k<<<leaf.nbox, FB * nw, sh_l, s>>>(p, kappa, 1, col, leaf_start.p, leaf_cnt.p, nbp.p, nbi.p,
+                                     leaf.cx.p, leaf.cy.p, leaf.L.p, xs.p, ys.p, qx.p, qy.p, perm.p,
+                                     tab, partial, stop);
   YQ_HIP(hipGetLastError());
 }
 
