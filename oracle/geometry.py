@@ -33,7 +33,12 @@ class Params:
     near_beta: a non-QBX panel J is near a target when the smallest distance
         from the target to one of J's nodes is below near_beta * h_J;
     near_nsub: sub-panels for the oversampled direct rule of such panels;
-    pot_nsub: sub-panels for off-surface targets closer than pot_beta * h_J.
+    pot_nsub: sub-panels for off-surface targets closer than pot_beta * h_J;
+    eta: coupling of the combined representation u = D[sigma] + eta S[sigma]
+        (the Brakhage-Werner form of eq. bwform written for the screened
+        equation: with k = i kappa the coupling is real; reading used: eta >= 0,
+        eta = 0 is the double layer of eq. intrep).  The second-kind equation
+        becomes 1/2 sigma + D sigma + eta S sigma = f.
     """
 
     panels: int = 16
@@ -46,6 +51,7 @@ class Params:
     near_nsub: int = 4
     pot_nsub: int = 8
     pot_beta: float = 0.5
+    eta: float = 0.0
 
 
 def gauss_legendre(q: int):

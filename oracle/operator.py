@@ -13,8 +13,25 @@ from __future__ import annotations
 
 import numpy as np
 
-from .kernels import dl_kernel, dl_grad_kernel
+from .kernels import dl_kernel, dl_grad_kernel, sl_kernel, sl_grad_kernel
 from .qbx import near_panels, qbx_row, operator_qbx_row, oversampled_row
+
+
+def layer_kernel(disc, x, y, ny):
+    """The kernel of the representation: dG/dnu_y, plus eta G for the combined
+    form D + eta S (eq. bwform; eta = params.eta, 0 for eq. intrep)."""
+    k = dl_kernel(x, y, ny, disc.kappa)
+    if disc.params.eta != 0.0:
+        k = k + disc.params.eta * sl_kernel(x, y, disc.kappa)
+    return k
+
+
+def layer_grad_kernel(disc, x, y, ny):
+    gx, gy = dl_grad_kernel(x, y, ny, disc.kappa)
+    if disc.params.eta != 0.0:
+        sx, sy = sl_grad_kernel(x, y, disc.kappa)
+        gx, gy = gx + disc.params.eta * sx, gy + disc.params.eta * sy
+    return gx, gy
 
 
 def _panel_cols(disc, J):
@@ -31,9 +48,9 @@ def build_matrices(disc, gradient=False, chunk=512):
     for s in range(0, N, chunk):
         e = min(N, s + chunk)
         xi = disc.x[s:e, None, :]
-        A[s:e] = disc.w[None, :] * dl_kernel(xi, disc.x[None, :, :], disc.normal[None, :, :], disc.kappa)
+        A[s:e] = disc.w[None, :] * layer_kernel(disc, xi, disc.x[None, :, :], disc.normal[None, :, :])
         if gradient:
-            gx, gy = dl_grad_kernel(xi, disc.x[None, :, :], disc.normal[None, :, :], disc.kappa)
+            gx, gy = layer_grad_kernel(disc, xi, disc.x[None, :, :], disc.normal[None, :, :])
             Gx[s:e] = disc.w[None, :] * gx
             Gy[s:e] = disc.w[None, :] * gy
     for i in range(N):
@@ -66,7 +83,7 @@ def far_rows(disc, rows, sigma):
     near corrections): out_i = sum_{j != i} w_j dG/dnu_y(x_i, y_j) sigma_j."""
     out = np.empty(len(rows))
     for a, i in enumerate(rows):
-        k = disc.w * dl_kernel(disc.x[i][None, :], disc.x, disc.normal, disc.kappa)
+        k = disc.w * layer_kernel(disc, disc.x[i][None, :], disc.x, disc.normal)
         k[i] = 0.0
         out[a] = k @ sigma
     return out
@@ -75,7 +92,7 @@ def far_rows(disc, rows, sigma):
 def far_grad_rows(disc, rows, sigma):
     out = np.empty((len(rows), 2))
     for a, i in enumerate(rows):
-        gx, gy = dl_grad_kernel(disc.x[i][None, :], disc.x, disc.normal, disc.kappa)
+        gx, gy = layer_grad_kernel(disc, disc.x[i][None, :], disc.x, disc.normal)
         gx = disc.w * gx
         gy = disc.w * gy
         gx[i] = 0.0
@@ -92,9 +109,9 @@ def apply_rows(disc, rows, sigma, gradient=False):
     grads = np.empty((len(rows), 2))
     for a, i in enumerate(rows):
         qp, extra = near_panels(disc, i)
-        k = disc.w * dl_kernel(disc.x[i][None, :], disc.x, disc.normal, disc.kappa)
+        k = disc.w * layer_kernel(disc, disc.x[i][None, :], disc.x, disc.normal)
         if gradient:
-            gx, gy = dl_grad_kernel(disc.x[i][None, :], disc.x, disc.normal, disc.kappa)
+            gx, gy = layer_grad_kernel(disc, disc.x[i][None, :], disc.x, disc.normal)
             gx = disc.w * gx
             gy = disc.w * gy
         mask = np.ones(disc.N, dtype=bool)

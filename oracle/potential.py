@@ -1,4 +1,5 @@
-"""Off-surface potential u = D[sigma] (eq. intrep; oracle step O7).
+"""Off-surface potential u = D[sigma] (eq. intrep; oracle step O7), or
+u = D[sigma] + eta S[sigma] for the combined form (eq. bwform, params.eta).
 
 Reading used: at a target z every panel J is summed with the plain q-point
 rule when the nearest node of J is at least pot_beta * h_J away, and with
@@ -9,7 +10,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .kernels import dl_kernel
+from .operator import layer_kernel
 from .qbx import oversampled_row
 
 
@@ -18,7 +19,7 @@ def eval_potential(disc, sigma, targets):
     q = disc.params.q
     out = np.empty(targets.shape[0])
     for a, z in enumerate(targets):
-        k = disc.w * dl_kernel(z[None, :], disc.x, disc.normal, disc.kappa)
+        k = disc.w * layer_kernel(disc, z[None, :], disc.x, disc.normal)
         d2 = ((disc.x - z) ** 2).sum(axis=1).reshape(-1, q).min(axis=1)
         near = np.nonzero(d2 < (disc.params.pot_beta * disc.panel_h) ** 2)[0]
         mask = np.ones(disc.N, dtype=bool)

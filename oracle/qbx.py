@@ -14,6 +14,12 @@ so the double layer of density sigma has, about a centre c, the local expansion
     alpha_l = (1/2pi) int d/dnu_y [K_l(kappa r_y) e^{i l th_y}] sigma(y) ds_y,
     d/dnu [K_l(kappa r) e^{i l th}] = e^{i l th} [kappa K_l'(kappa r) (rhat.nu) + (i l / r) K_l(kappa r) (thhat.nu)],
 
+and the single layer (eq. single-layer-def) the same expansion with
+alpha_l = (1/2pi) int K_l(kappa r_y) e^{i l th_y} sigma(y) ds_y; the combined
+representation D + eta S (eq. bwform, params.eta) adds eta times those.  The single
+layer is continuous across the boundary, so both one-sided expansions carry it,
+and their mean below keeps it.
+
 with (r, th) polar coordinates about c.  Readings used (the paper defers the
 details to the GIGAQBX references):
 
@@ -53,7 +59,7 @@ import numpy as np
 from scipy import special
 
 from .geometry import gauss_legendre, panel_nodes
-from .kernels import dl_kernel, dl_grad_kernel
+from .kernels import dl_kernel, dl_grad_kernel, sl_kernel, sl_grad_kernel
 
 
 def interp_matrix(src, dst):
@@ -138,6 +144,8 @@ def qbx_row(disc, i, side=1, gradient=False):
         Klp = special.kvp(ls[:, None], kap * ry[None, :])
         dK = np.exp(1j * ls[:, None] * thy[None, :]) * (
             kap * Klp * rn[None, :] + (1j * ls[:, None] / ry[None, :]) * Kl * tn[None, :])
+        if prm.eta != 0.0:
+            dK = dK + prm.eta * np.exp(1j * ls[:, None] * thy[None, :]) * Kl
         coef = dK * (wy / (2.0 * np.pi))[None, :]                         # (2p+1, F)
         cf = np.real((val_fac[:, None] * coef).sum(axis=0))
         vals[j] = cf @ L
@@ -162,8 +170,9 @@ def operator_qbx_row(disc, i):
 
 
 def oversampled_row(disc, x, J, nsub, gradient=False):
-    """Weights of sigma on panel J for the double layer at point x, by an nsub-fold
-    oversampled Gauss-Legendre rule with interpolated sigma."""
+    """Weights of sigma on panel J for the double layer (plus eta times the single
+    layer) at point x, by an nsub-fold oversampled Gauss-Legendre rule with
+    interpolated sigma."""
     prm = disc.params
     P, q = prm.panels, prm.q
     pid = J // P
@@ -171,8 +180,14 @@ def oversampled_row(disc, x, J, nsub, gradient=False):
     y, ny, wy, xi = panel_nodes(disc.center[pid], disc.angle[pid], disc.axes[pid], k, P, q, nsub)
     L = _sub_interp(q, nsub)
     xx = np.broadcast_to(x, y.shape)
-    vals = (wy * dl_kernel(xx, y, ny, disc.kappa)) @ L
+    k = dl_kernel(xx, y, ny, disc.kappa)
+    if prm.eta != 0.0:
+        k = k + prm.eta * sl_kernel(xx, y, disc.kappa)
+    vals = (wy * k) @ L
     if not gradient:
         return vals
     gx, gy = dl_grad_kernel(xx, y, ny, disc.kappa)
+    if prm.eta != 0.0:
+        sx, sy = sl_grad_kernel(xx, y, disc.kappa)
+        gx, gy = gx + prm.eta * sx, gy + prm.eta * sy
     return vals, np.stack([(wy * gx) @ L, (wy * gy) @ L], axis=-1)
