@@ -118,6 +118,10 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--kappa", type=float, default=1.0)
+    ap.add_argument("--tol", type=float, default=1e-9,
+                    help="batch: relative residual tolerance of the mixed solves")
+    ap.add_argument("--error-configs", type=int, default=16,
+                    help="batch: configurations re-solved in FP64 to 1e-12 for the per-result errors")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=1536)
     ap.add_argument("--fp64-steps", type=int, default=3)
@@ -125,10 +129,11 @@ def parse():
                     help="only run a plain 256 MiB device-to-device copy (counter calibration)")
     ap.add_argument("--workload", choices=["medium", "batch", "serve", "large", "table2",
                                            "dynamics", "cutoff"],
-                    default="medium",
-                    help="medium: the 50-ellipse solve (default line); batch: many configurations "
-                         "per fused launch; serve: Poisson-arrival continuous batching")
-    ap.add_argument("--configs", type=int, default=128, help="batch: number of configurations")
+                    default="batch",
+                    help="batch: 1,024 configurations of 10-200 ellipses per batched solve "
+                         "(default line); medium: the 50-ellipse solve; serve: Poisson-arrival "
+                         "continuous batching")
+    ap.add_argument("--configs", type=int, default=1024, help="batch: number of configurations")
     ap.add_argument("--requests", type=int, default=2000, help="serve: number of requests")
     ap.add_argument("--rate", type=float, default=200.0, help="serve: arrival rate (1/s)")
     ap.add_argument("--nmax", type=int, default=None,
@@ -143,8 +148,9 @@ def parse():
     ap.add_argument("--fp64-requests", type=int, default=None,
                     help="serve: requests of the trace (from the start) replayed on the FP64 "
                          "one-at-a-time path (default all)")
-    ap.add_argument("--single-baseline", type=int, default=100000,
-                    help="batch: configurations also solved one at a time for comparison")
+    ap.add_argument("--single-baseline", type=int, default=128,
+                    help="batch: configurations (every k-th) also solved one at a time on the "
+                         "FP64 path for comparison")
     return ap.parse_args()
 
 
@@ -240,101 +246,267 @@ def cpu_baseline(cfg, rows):
                        f"numpy/scipy, {dt:.1f} s")
 
 
+def _batch_layout(item):
+    import workloads
+    return workloads.batched_layout(item)
+
+
+def batch_layouts(plan):
+    """Layouts of the batched workload's configurations, drawn in parallel host processes."""
+    from concurrent.futures import ProcessPoolExecutor
+    workers = max(1, min(16, os.cpu_count() or 1))
+    with ProcessPoolExecutor(workers) as ex:
+        return list(ex.map(_batch_layout, plan, chunksize=8))
+
+
+def _cpu_rows_job(job):
+    """One worker's share of the CPU baseline: the oracle's operator rows of one
+    configuration, timed on one thread."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    import oracle
+    import workloads
+    from oracle.geometry import Params
+    import warnings
+    warnings.simplefilter("ignore", RuntimeWarning)   # the self pair's 0/0, masked out
+    cfg, rows, seed = job
+    d = oracle.discretize(cfg, Params(panels=32, qbx_order=10))
+    sig = workloads.random_density(d.N, seed)
+    rows = [r % d.N for r in rows]
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        oracle.apply_rows(d, rows, sig)
+        dt = time.perf_counter() - t0
+    return len(rows) * d.N, dt
+
+
+def cpu_baseline_batch(cfgs, matvecs_per_solve, n_configs=32, rows_per_config=96):
+    """The oracle's operator rows (plain far sum + QBX rows) on rows drawn from
+    n_configs of the batched workload's configurations, in one process per host
+    core (16 at most); scaled to solves/s by the mean source-target pairs of one
+    solve of the GPU run (its matvecs per solve times N^2 per configuration)."""
+    import numpy as np
+    from concurrent.futures import ProcessPoolExecutor
+    workers = max(1, min(16, os.cpu_count() or 1))
+    pick = np.linspace(0, len(cfgs) - 1, n_configs).astype(int)
+    jobs = []
+    for k, c in enumerate(pick):
+        rows = np.random.default_rng(100 + k).integers(0, 1 << 30, rows_per_config).tolist()
+        jobs.append((cfgs[c], rows, 200 + k))
+    with ProcessPoolExecutor(workers) as ex:
+        list(ex.map(_cpu_rows_job, [(cfgs[0], [0], 1)] * workers))    # warm-up (imports)
+        t0 = time.perf_counter()
+        res = list(ex.map(_cpu_rows_job, jobs))
+        wall = time.perf_counter() - t0
+    inter = sum(r[0] for r in res)
+    rate = inter / wall
+    N = np.array([c.n * 512 for c in cfgs], dtype=float)
+    pairs_per_solve = float(np.mean(matvecs_per_solve * N * N))
+    return dict(value=rate / pairs_per_solve, unit="solves/s (estimate)", cores=workers,
+                kind="oracle", interactions_per_s=rate,
+                sample=f"{len(jobs) * rows_per_config} operator rows (each: N far-field pairs + "
+                       f"QBX window) from {len(jobs)} of the {len(cfgs)} configurations, one "
+                       f"single-threaded oracle process per core, {wall:.1f} s; solves/s = "
+                       f"interactions/s / {pairs_per_solve:.3e} pairs per solve (the GPU run's "
+                       f"mean matvecs per solve x N^2)")
+
+
+def errors_vs_oracle_c2(yq, tol):
+    """Per-result errors of the 50-ellipse workload's mixed solve (kappa 1) against
+    the oracle's stored dense-LU results (tests/golden/c2_kappa1.npz): density,
+    potential, force and torque, each max |x - x*| / max |x*| (reading R15)."""
+    import numpy as np
+    import workloads
+    path = os.path.join(ROOT, "tests", "golden", "c2_kappa1.npz")
+    if not os.path.exists(path):
+        return None
+    g = np.load(path)
+    cfg = workloads.config_medium(kappa=1.0, seed=0)
+    pb = yq.Problem(yq.default_params(panels_per_particle=32, qbx_order=10, tol=tol,
+                                      precision=yq.YQ_MIXED, maxiter=300))
+    pb.set_workload(cfg["particles"])
+    pb.set_boundary_data(pb.boundary_label())
+    sig, info, F, T, E = pb.solve_forces()
+    u = pb.eval_potential(sig, g["targets"])
+    rel = lambda a, b: float(np.abs(a - b).max() / np.abs(b).max())
+    return {"workload": "50 ellipses N=25600 kappa=1, mixed, tol %g" % tol,
+            "density": rel(sig.cpu().numpy(), g["sigma"]),
+            "potential": rel(u.cpu().numpy(), g["potential"]),
+            "force": rel(F.cpu().numpy().reshape(-1, 2), g["force"]),
+            "torque": rel(T.cpu().numpy(), g["torque"]),
+            "energy": abs(E - float(g["energy"])) / abs(float(g["energy"]))}
+
+
 def bench_batch(args):
-    """Many configurations per fused launch (log-uniform 10..nmax ellipses each)."""
+    """The batched workload: many configurations of log-uniform 10..nmax ellipses.
+
+    One step = one batched mixed-precision solve of every configuration plus the
+    forces and torques of every particle.  Configurations below the FMM-lane
+    threshold run in the fused engine (one persistent far-field launch per GMRES
+    iteration for all of them, the iteration replayed from captured hipGraphs);
+    larger ones are solved by lane workers with the FMM far field beside it.
+    Set-up (geometry, near lists, QBX correction, trees) is done once before the
+    timed region."""
     import numpy as np
     import torch
 
     import paper_1810_04131_amd as yq
     import workloads
     nmax = args.nmax or 200
-    cfgs = workloads.batched_configs(args.configs, seed=0, nmax=nmax)
+    log = lambda msg: print(f"# {msg}", file=sys.stderr, flush=True)
+    plan = workloads.batched_plan(args.configs, seed=0, nmax=nmax)
+    t0 = time.perf_counter()
+    cfgs = batch_layouts(plan)
+    log(f"{len(cfgs)} configurations drawn in {time.perf_counter() - t0:.1f} s")
     hybrid = args.batch_lane == "hybrid"
     thr = args.fmm_min_nodes if hybrid else None
-    prm = yq.default_params(panels_per_particle=32, qbx_order=10, tol=1e-8,
+    tol = args.tol
+    prm = yq.default_params(panels_per_particle=32, qbx_order=10, tol=tol,
                             precision=yq.YQ_MIXED, restart=60, maxiter=300)
-    log = lambda msg: print(f"# {msg}", file=sys.stderr, flush=True)
-    log(f"{len(cfgs)} configurations drawn")
     b = yq.Batch(prm)
     if hybrid:
         b.set_fmm(thr, workers=args.fmm_workers)
     t0 = time.perf_counter()
     b.set_configs(cfgs)
     t_setup = time.perf_counter() - t0
-    log(f"set-up {t_setup:.1f} s, {b.total} nodes")
+    N = np.diff(b.offsets).astype(float)
+    lane = N >= thr if hybrid else np.zeros(len(cfgs), dtype=bool)
+    log(f"set-up {t_setup:.1f} s, {b.total} nodes, {int(lane.sum())} configurations in the FMM lane")
     pblk, fwant = b.autotune()
     log(f"autotuned: persistent blocks {pblk}, far_want {fwant}")
     b.set_boundary_data(b.boundary_label())
-    b.solve()                                   # warm-up (captures the iteration graph)
-    log("warm-up solve done")
+    b.profile(True)      # events around every fused far-field launch (split iteration graphs)
+
+    def step():
+        sig, infos = b.solve()
+        F, T, E = b.forces(sig)
+        return sig, infos, F, T, E
+
+    for k in range(max(args.warmup, 1)):
+        step()
+        log(f"warm-up step {k + 1} done")
+    for prec in (yq.YQ_MIXED, yq.YQ_FP64):
+        b.profile_read(prec, reset=True)
     lat = []
+    torch.cuda.synchronize()
+    t_all = time.perf_counter()
     for k in range(max(args.steps, 1)):
         t0 = time.perf_counter()
-        sig, infos = b.solve()
+        sig, infos, F, T, E = step()
+        torch.cuda.synchronize()
         lat.append(time.perf_counter() - t0)
-        log(f"timed solve {k + 1}: {lat[-1]:.2f} s")
-    F, T, E = b.forces(sig)
-    torch.cuda.synchronize()
-    N = np.diff(b.offsets).astype(float)
+        log(f"timed step {k + 1}: {lat[-1]:.2f} s")
+    t_all = time.perf_counter() - t_all
+    n32, ms32, pairs32 = b.profile_read(yq.YQ_MIXED)
+    n64, ms64, pairs64 = b.profile_read(yq.YQ_FP64)
     its = np.array([i["iterations"] for i in infos])
     ref = np.array([i["outer_steps"] for i in infos])
+    mv = np.array([i["matvecs_fp32"] + i["matvecs_fp64"] for i in infos], dtype=float)
     resid = max(i["residual"] for i in infos)
-    # one fused FP32 far-field pass evaluates sum_c N_c^2 pairs over the engine's
-    # members; time it alone on a fused-only batch of the same configurations
-    if hybrid:
-        b.close()
-        b = yq.Batch(prm)
-        b.set_configs(cfgs)
-        b.autotune()
-    s = torch.randn(b.total, dtype=torch.float64, device="cuda")
-    b.apply_operator(s, yq.YQ_MIXED)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(3):
-        b.apply_operator(s, yq.YQ_MIXED)
-    torch.cuda.synchronize()
-    t_mv = (time.perf_counter() - t0) / 3
-    pairs = float((N * N).sum())
+    sig = sig.cpu().numpy()
+    F, T = F.cpu().numpy().reshape(-1, 2), T.cpu().numpy()
+    poff = np.concatenate([[0], np.cumsum(b.nparticles)])
+    offs = b.offsets.copy()
     b.close()
-    t_solve = percentile(lat, 0.5)
-    # one at a time, same solver and per-size far field, on the first configurations
-    k1 = min(args.single_baseline, len(cfgs))
-    t_single = 0.0
-    prm_fmm = yq.default_params(panels_per_particle=32, qbx_order=10, tol=1e-8,
-                                precision=yq.YQ_MIXED, restart=60, maxiter=300,
-                                far_mode=yq.YQ_FAR_FMM)
-    for k, c in enumerate(cfgs[:k1]):
-        if k % 128 == 0:
-            log(f"one at a time: {k} of {k1}")
-        pb = yq.Problem(prm_fmm if hybrid and c.n * 512 >= thr else prm)
-        t0 = time.perf_counter()
-        pb.set_workload(c)
+
+    def single(c, p):
+        pb = yq.Problem(p)
+        pb.set_workload(cfgs[c])
         pb.set_boundary_data(pb.boundary_label())
-        pb.solve()
+        s, _ = pb.solve()
+        Fs, Ts, _ = pb.forces(s)
+        return s, Fs, Ts
+
+    def p64(t, fmm):
+        kw = dict(far_mode=yq.YQ_FAR_FMM) if fmm else {}
+        return yq.default_params(panels_per_particle=32, qbx_order=10, tol=t,
+                                 precision=yq.YQ_FP64, restart=60, maxiter=400, **kw)
+
+    # FP64 one-at-a-time path: each configuration alone (FP64 solve to the same
+    # tolerance with the direct far field below the lane threshold and the FP64
+    # FMM above, then its forces), on every k-th configuration
+    stride = max(1, len(cfgs) // max(args.single_baseline, 1))
+    sample = list(range(0, len(cfgs), stride))
+    service = []
+    for k, c in enumerate(sample):
         torch.cuda.synchronize()
-        t_single += time.perf_counter() - t0
+        a = time.perf_counter()
+        single(c, p64(tol, lane[c]))
+        torch.cuda.synchronize()
+        service.append(time.perf_counter() - a)
+        if (k + 1) % 64 == 0:
+            log(f"FP64 one at a time: {k + 1} of {len(sample)}")
+    service = np.array(service)
+    t_one = float(service.mean()) * len(cfgs)     # all configurations, one after another
+    # per-result errors of the batch against FP64 solves to 1e-12 (the FP64 path
+    # matches the oracle's LU to 1e-10 in the parity tests)
+    err = {"density": 0.0, "force": 0.0, "torque": 0.0}
+    ref_idx = list(range(0, len(cfgs), max(1, len(cfgs) // args.error_configs)))
+    for c in ref_idx:
+        s64, F64, T64 = single(c, p64(1e-12, lane[c]))
+        s64, F64, T64 = s64.cpu().numpy(), F64.cpu().numpy().reshape(-1, 2), T64.cpu().numpy()
+        err["density"] = max(err["density"], float(np.abs(sig[offs[c]:offs[c + 1]] - s64).max()
+                                                   / np.abs(s64).max()))
+        err["force"] = max(err["force"], float(np.abs(F[poff[c]:poff[c + 1]] - F64).max()
+                                               / np.abs(F64).max()))
+        err["torque"] = max(err["torque"], float(np.abs(T[poff[c]:poff[c + 1]] - T64).max()
+                                                 / np.abs(T64).max()))
+    t_step = percentile(lat, 0.5)
+    # roofline of the fused FP32 far-field kernel: algorithmic flops = 40 per
+    # source-target pair (the design's count for the FP32 kernel evaluation);
+    # pairs = what the timed launches evaluated (configurations still iterating)
+    F32_ALG, F64_ALG = 40.0, 50.0
+    avg32 = ms32 / max(n32, 1)
+    achieved = F32_ALG * pairs32 / (ms32 * 1e-3) if ms32 > 0 else 0.0
     out = {
         "metric": "source-target interactions/s per matvec; solves/s + p50/p99 latency at 1e-8 rel err",
-        "value": pairs / t_mv, "unit": "interactions/s", "n_gpus": 1, "steps": len(lat),
-        "warmup": 1, "ms_per_step": t_solve * 1e3, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "value": len(cfgs) / t_step, "unit": "solves/s", "n_gpus": 1, "steps": len(lat),
+        "warmup": max(args.warmup, 1), "ms_per_step": t_all / len(lat) * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
+        "data": "synthetic",
         "config": {"workload": f"batched: {len(cfgs)} configurations of 10-{nmax} ellipses "
-                               f"(log-uniform), 32x16 nodes per particle, kappa~U[0.5,2], "
-                               f"QBX order 10, mixed FP32/FP64 to 1e-8; "
-                               + (f"fused direct engine below {thr} nodes, FMM lane "
-                                  f"({args.fmm_workers} workers) above" if hybrid
+                               f"(log-uniform, box 30 sqrt(n/50), gap 0.2), 32x16 nodes per "
+                               f"particle, kappa~U[0.5,2], QBX order 10, mixed FP32/FP64 to a "
+                               f"relative residual of {tol:g}; one step = batched solve + "
+                               f"forces/torques of every configuration; "
+                               + (f"{int((~lane).sum())} configurations below {thr} nodes in the "
+                                  f"fused direct engine (graph-replayed iteration), "
+                                  f"{int(lane.sum())} from {thr} nodes on in the FMM lane "
+                                  f"({args.fmm_workers} workers, FMM order 20 inner / 40 FP64 "
+                                  f"residuals)" if hybrid
                                   else "every configuration in the fused direct engine"),
                    "configs": len(cfgs), "total_nodes": int(N.sum()),
                    "parallelism": "single GPU"},
-        "solves_per_s": len(cfgs) / t_solve,
-        "batch_latency_ms_p50": t_solve * 1e3, "batch_latency_ms_p99": percentile(lat, 0.99) * 1e3,
+        "solves_per_s": len(cfgs) / t_step,
+        "latency_ms_p50": percentile(lat, 0.5) * 1e3, "latency_ms_p99": percentile(lat, 0.99) * 1e3,
         "setup_s": t_setup, "autotune": {"persist_blocks": pblk, "far_want": fwant},
-        "fused_far32_pass_ms": t_mv * 1e3, "pairs_per_fused_pass": pairs,
         "gmres_iterations_mean": float(its.mean()), "gmres_iterations_max": int(its.max()),
         "refine_steps_max": int(ref.max()), "residual_max": resid,
-        "one_at_a_time_solves_per_s": k1 / t_single if t_single else None,
-        "one_at_a_time_sample": k1,
+        "matvec_interactions_per_s_fp32": pairs32 / (ms32 * 1e-3) if ms32 > 0 else None,
+        "matvec_interactions_per_s_fp64": pairs64 / (ms64 * 1e-3) if ms64 > 0 else None,
+        "fp64_one_at_a_time": {"sample": len(sample), "of": len(cfgs),
+                               "solves_per_s": len(cfgs) / t_one,
+                               "latency_ms_p50": float(np.percentile(service, 50)) * 1e3,
+                               "latency_ms_p99": float(np.percentile(service, 99)) * 1e3,
+                               "all_configs_one_after_another_ms": t_one * 1e3},
+        "errors_vs_fp64_path": dict(err, configs=len(ref_idx), reference="FP64 solve to 1e-12"),
+        "errors_vs_oracle": errors_vs_oracle_c2(yq, tol),
+        "roofline": {"bound": "alu", "kernel": "bfar32_kernel", "achieved": achieved / 1e12,
+                     "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32,
+                     "traffic": None, "flops_per_pair": F32_ALG,
+                     "pairs_per_launch": pairs32 / max(n32, 1), "avg_launch_ms": avg32,
+                     "launches": n32,
+                     "fp64_kernel": {"kernel": "bfar64_kernel", "launches": n64,
+                                     "avg_launch_ms": ms64 / max(n64, 1),
+                                     "achieved": F64_ALG * pairs64 / (ms64 * 1e-3) / 1e12
+                                     if ms64 > 0 else None,
+                                     "peak": PEAK_FP64 / 1e12,
+                                     "frac": F64_ALG * pairs64 / (ms64 * 1e-3) / PEAK_FP64
+                                     if ms64 > 0 else None}},
     }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_batch(cfgs, mv)
     print(json.dumps(out), flush=True)
 
 

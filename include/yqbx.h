@@ -101,6 +101,17 @@ typedef struct yq_params {
                                   of the gradient bound that of every gradient <= eps kappa
                                   ||sigma||_inf.  The FP32 inner operator of YQ_MIXED uses
                                   max(eps, inner_tol / 10).  0 < cutoff_tol < 1 */
+  double sl_coupling;          /* eta >= 0: the combined representation u = D[sigma] + eta S[sigma]
+                                  (the Brakhage-Werner form of eq. bwform with the real coupling
+                                  of the screened equation; S the single layer of eq.
+                                  single-layer-def), solved through 1/2 sigma + D sigma +
+                                  eta S sigma = f.  For large rho (small kappa) 1/2 I + D tends to
+                                  the Laplace double layer, which loses one dimension per particle;
+                                  eta > 0 keeps the system well conditioned.  0 (default): the
+                                  double layer of eq. intrep.  eta > 0 needs far_mode
+                                  YQ_FAR_DIRECT and single problems (the batch and the server
+                                  reject it); the far field then evaluates K0 and K1 at every pair
+                                  (FP64, or FP32 for the inner operator of YQ_MIXED) */
 } yq_params;
 
 typedef struct yq_solve_info {
@@ -115,7 +126,8 @@ typedef struct yq_solve_info {
 /* Defaults: P = 32, p = 10, window 2, oversample 4, radius 0.25, near_beta 0.5,
  * near_oversample 4, pot_oversample 8, pot_beta 0.5, FP64, direct far field,
  * FMM order 20 / 64 per leaf, tol 1e-10, maxiter 200, restart 100,
- * inner_tol 1e-6, max_refine 8, fmm_resid_order 40, fmm_m2l YQ_M2L_MFMA, cutoff_tol 1e-12. */
+ * inner_tol 1e-6, max_refine 8, fmm_resid_order 40, fmm_m2l YQ_M2L_MFMA, cutoff_tol 1e-12,
+ * sl_coupling 0. */
 void yq_default_params(yq_params* params);
 
 /* Creates a problem on the current HIP device.  params: host, copied. */
@@ -344,6 +356,20 @@ int yq_batch_autotune(yq_batch* batch, int32_t* persist_blocks, int32_t* far_wan
 /* enable != 0: replay the captured iteration graph (default); 0: launch eagerly. */
 int yq_batch_use_graphs(yq_batch* batch, int32_t enable);
 
+/* Timers of the fused engine's far-field launches (the FP32 kernel of the inner
+ * iterations and the FP64 kernel of the refinement residuals).  enable != 0:
+ * every launch is bracketed by hipEvents on the batch's stream (the captured
+ * iteration is then replayed as three graphs, with the events recorded between
+ * the launch of the far-field kernel's graph and its neighbours) and the launches
+ * count the source-target pairs they evaluate (masked configurations excluded).
+ * yq_batch_profile_read synchronises and returns, for YQ_MIXED (FP32 kernel) or
+ * YQ_FP64, the number of timed launches, their summed duration (ms) and the
+ * summed pairs; reset != 0 clears them.  Configurations of the FMM lane are not
+ * counted.  Both synchronous. */
+int yq_batch_profile_enable(yq_batch* batch, int32_t enable);
+int yq_batch_profile_read(yq_batch* batch, int32_t precision, int64_t* launches,
+                          double* total_ms, double* pairs, int32_t reset);
+
 /* ---- Serving -----------------------------------------------------------------------------
  * A continuous-batching solve server on one GPU.  Requests (one particle
  * configuration each) are queued by yq_server_submit and advanced by
@@ -414,6 +440,14 @@ int yq_server_cancel(yq_server* server, int64_t ticket);
 int yq_profile_enable(yq_problem* prob, int32_t phase_mask);
 int yq_profile_read(yq_problem* prob, int32_t phase, int64_t* launches, double* total_ms,
                     int32_t reset);
+
+/* The FMM's adaptive quadtree (far_mode FMM or AUTO above its threshold): a box is
+ * split while it holds more than fmm_leaf_max nodes, so leaves sit on different
+ * levels.  Host outputs (each may be NULL): depth (deepest level), leaves, the
+ * largest leaf's node count, the source-target pairs of one direct (P2P) pass
+ * and the box pairs of one M2L pass.  YQ_ESTATE when the problem has no FMM. */
+int yq_fmm_stats(const yq_problem* prob, int32_t* depth, int32_t* leaves, int32_t* max_leaf,
+                 double* p2p_pairs, double* m2l_pairs);
 
 /* Device special functions, for testing: kind 0 -> K0(z), 1 -> K1(z),
  * 2 -> K_order(z), 3 -> I_order(z); precision YQ_FP64 or YQ_MIXED (FP32).

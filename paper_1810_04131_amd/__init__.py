@@ -218,6 +218,15 @@ class Problem:
                                               a.ctypes.data_as(ctypes.c_void_p)))
         return c.reshape(self.n, 2), a
 
+    def fmm_stats(self):
+        """The FMM quadtree: depth, leaves, largest leaf, P2P pairs and M2L box pairs per pass."""
+        d, nl, ml = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        pp, mp = ctypes.c_double(), ctypes.c_double()
+        self._check(self.lib.yq_fmm_stats(self.h, ctypes.byref(d), ctypes.byref(nl), ctypes.byref(ml),
+                                          ctypes.byref(pp), ctypes.byref(mp)))
+        return dict(depth=d.value, leaves=nl.value, max_leaf=ml.value, p2p_pairs=pp.value,
+                    m2l_pairs=mp.value)
+
     def eval_potential(self, sigma, targets):
         sigma = self._dev(sigma)
         t = self._dev(targets).reshape(-1, 2)
@@ -346,6 +355,18 @@ class Batch:
 
     def use_graphs(self, enable=True):
         self._check(self.lib.yq_batch_use_graphs(self.h, int(bool(enable))))
+
+    def profile(self, enable=True):
+        """Timers of the fused far-field launches (see yq_batch_profile_enable)."""
+        self._check(self.lib.yq_batch_profile_enable(self.h, int(bool(enable))))
+
+    def profile_read(self, precision=YQ_MIXED, reset=True):
+        """(launches, total ms, source-target pairs) of the timed far-field launches."""
+        n, ms, pairs = ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
+        self._check(self.lib.yq_batch_profile_read(self.h, int(precision), ctypes.byref(n),
+                                                   ctypes.byref(ms), ctypes.byref(pairs),
+                                                   int(bool(reset))))
+        return int(n.value), float(ms.value), float(pairs.value)
 
     def segment(self, v, c):
         return v[int(self.offsets[c]):int(self.offsets[c + 1])]

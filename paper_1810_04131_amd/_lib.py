@@ -58,6 +58,7 @@ class yq_params(ctypes.Structure):
         ("fmm_resid_order", c_int32),
         ("fmm_m2l", c_int32),
         ("cutoff_tol", c_double),
+        ("sl_coupling", c_double),
     ]
 
 
@@ -113,6 +114,9 @@ SIGNATURES = {
                           P, P]),
     "yq_get_particles": (c_int32, [P, P, P]),
     "yq_bessel": (c_int32, [c_int32, c_int32, c_int32, c_int64, P, P]),
+    "yq_fmm_stats": (c_int32, [P, ctypes.POINTER(c_int32), ctypes.POINTER(c_int32),
+                               ctypes.POINTER(c_int32), ctypes.POINTER(c_double),
+                               ctypes.POINTER(c_double)]),
     "yq_batch_create": (c_int32, [ctypes.POINTER(yq_params), ctypes.POINTER(c_void_p)]),
     "yq_batch_destroy": (None, [P]),
     "yq_batch_last_error": (c_char_p, [P]),
@@ -126,6 +130,9 @@ SIGNATURES = {
     "yq_batch_forces": (c_int32, [P, P, c_double, P, P, P]),
     "yq_batch_autotune": (c_int32, [P, ctypes.POINTER(c_int32), ctypes.POINTER(c_int32)]),
     "yq_batch_use_graphs": (c_int32, [P, c_int32]),
+    "yq_batch_profile_enable": (c_int32, [P, c_int32]),
+    "yq_batch_profile_read": (c_int32, [P, c_int32, ctypes.POINTER(c_int64), ctypes.POINTER(c_double),
+                                        ctypes.POINTER(c_double), c_int32]),
     "yq_server_create": (c_int32, [ctypes.POINTER(yq_params), c_int64, c_int32, c_double,
                                    ctypes.POINTER(c_void_p)]),
     "yq_server_destroy": (None, [P]),

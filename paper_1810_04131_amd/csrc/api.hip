@@ -92,6 +92,10 @@ void check_params(const yq_params& p) {
              YQ_EINVAL, "bad far_mode");
   YQ_REQUIRE(p.far_mode != YQ_FAR_CUTOFF || (p.cutoff_tol > 0.0 && p.cutoff_tol < 1.0), YQ_EINVAL,
              "cutoff_tol must be in (0, 1)");
+  YQ_REQUIRE(std::isfinite(p.sl_coupling) && p.sl_coupling >= 0.0, YQ_EINVAL,
+             "sl_coupling must be finite and >= 0");
+  YQ_REQUIRE(p.sl_coupling == 0.0 || p.far_mode == YQ_FAR_DIRECT, YQ_EINVAL,
+             "the combined representation (sl_coupling > 0) needs the direct far field");
   YQ_REQUIRE(p.fmm_order >= 1 && p.fmm_order <= MAXP_FMM, YQ_EINVAL, "fmm_order out of range 1..48");
   YQ_REQUIRE(p.fmm_resid_order >= 0 && p.fmm_resid_order <= MAXP_FMM, YQ_EINVAL,
              "fmm_resid_order out of range 0..48");
@@ -143,9 +147,13 @@ void apply_op(yq_problem* pb, const double* sigma, double* out, int prec) {
     return;
   }
   if (prec == YQ_MIXED) {
-    if (pb->src_for != sigma) pb->pack32(sigma);   // else packed by the Arnoldi step
-    pb->src_for = nullptr;
-    {
+    if (g.eta > 0.0) {
+      // combined representation: both layers in one pass (FP32 arithmetic)
+      LaunchTimed t(pb, 1);
+      launch_far_sd(g, sigma, pb->fp, nullptr, pb->partial32.p, pb->stream, pb->stop_dev, t.a, t.b);
+    } else {
+      if (pb->src_for != sigma) pb->pack32(sigma);   // else packed by the Arnoldi step
+      pb->src_for = nullptr;
       LaunchTimed t(pb, 1);
       launch_far32(pb->far32(), pb->fp, pb->partial32.p, pb->stream, pb->stop_dev, t.a, t.b);
     }
@@ -155,7 +163,10 @@ void apply_op(yq_problem* pb, const double* sigma, double* out, int prec) {
   } else {
     {
       LaunchTimed t(pb, 0);
-      launch_far64(g, sigma, pb->fp, pb->partial.p, pb->stream, pb->stop_dev, t.a, t.b);
+      if (g.eta > 0.0)
+        launch_far_sd(g, sigma, pb->fp, pb->partial.p, nullptr, pb->stream, pb->stop_dev, t.a, t.b);
+      else
+        launch_far64(g, sigma, pb->fp, pb->partial.p, pb->stream, pb->stop_dev, t.a, t.b);
     }
     Timed t(pb, 2);
     launch_finish(g, win, pb->fp, pb->partial.p, nullptr, pb->W.p, pb->xrow.p, pb->xpan.p,
@@ -249,7 +260,8 @@ int arnoldi_pipelined(yq_problem* pb, int prec, int maxsteps, double beta, doubl
   double* hst = (double*)pb->hstat.p;            // host copy of the status [4 m]
   launch_gmres_init(dg, m, beta, stop, s);
   pb->stop_dev = stop;
-  const bool pack = prec == YQ_MIXED && !pb->fmm;   // the next matvec packs FP32 sources
+  // the next matvec packs FP32 sources (the combined representation reads sigma itself)
+  const bool pack = prec == YQ_MIXED && !pb->fmm && pb->prm.sl_coupling == 0.0;
   int queued = 0, stopped = -1;
   for (int j = 0; j < maxsteps; ++j) {
     double* vj = V + (int64_t)j * N;
@@ -372,6 +384,7 @@ void ensure_krylov(yq_problem* pb) {
   pb->gstop.reserve(1);
   pb->hstat.fit((size_t)4 * m * sizeof(double));
   pb->hpart.fit((size_t)krylov_blocks(N) * sizeof(double));
+  pb->delta.fit(N);   // refinement correction (mixed solves)
   for (auto& e : pb->step_ev)
     if (!e) YQ_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
 }
@@ -410,6 +423,7 @@ void yq_default_params(yq_params* p) {
   p->fmm_resid_order = 40;
   p->fmm_m2l = YQ_M2L_MFMA;
   p->cutoff_tol = 1e-12;
+  p->sl_coupling = 0.0;
 }
 
 const char* yq_error_string(int status) {
@@ -840,11 +854,15 @@ int yq_apply_far(yq_problem* pb, const double* sigma, double* out, int32_t preci
       return;
     }
     // far field with a zero near correction: reuse finish with window 0 rows skipped
-    if (precision == YQ_MIXED) {
+    if (g.eta > 0.0) {
+      launch_far_sd(g, sigma, pb->fp, precision == YQ_MIXED ? nullptr : pb->partial.p,
+                    precision == YQ_MIXED ? pb->partial32.p : nullptr, pb->stream);
+    } else if (precision == YQ_MIXED) {
       pb->pack32(sigma);
       launch_far32(pb->far32(), pb->fp, pb->partial32.p, pb->stream);
-    } else
+    } else {
       launch_far64(g, sigma, pb->fp, pb->partial.p, pb->stream);
+    }
     launch_finish(g, -1, pb->fp, precision == YQ_MIXED ? nullptr : pb->partial.p,
                   precision == YQ_MIXED ? pb->partial32.p : nullptr, pb->W.p, pb->xrow.p,
                   pb->xpan.p, nullptr, sigma, out, pb->stream);
@@ -886,7 +904,8 @@ int solve_impl(yq_problem* pb, const double* sigma0, double* sigma, yq_solve_inf
     bool r_current = false;  // r holds f - A sigma (FP64 operator) for the current sigma
     double* r = pb->kd.p;    // refinement residual
     pb->grad_ready = false;
-    fuse = fuse && pb->prm.precision == YQ_MIXED && !pb->fmm && !pb->fmm_hi;
+    fuse = fuse && pb->prm.precision == YQ_MIXED && !pb->fmm && !pb->fmm_hi &&
+           pb->prm.sl_coupling == 0.0;
     bool expect_last = false;  // the next residual is expected to meet the tolerance
     double last_rel = -1.0;    // mixed: |f - A sigma| / |f| of the current residual r
     if (pb->prm.precision == YQ_FP64) {
@@ -987,7 +1006,10 @@ FarPlan far_grad(yq_problem* pb, const double* sigma) {
     return one;
   }
   pb->gpartial.reserve((size_t)pb->fp.chunks * 2 * pb->N);
-  launch_far_grad64(pb->view(), sigma, pb->fp, pb->gpartial.p, pb->stream);
+  if (pb->prm.sl_coupling > 0.0)
+    launch_far_sd_grad64(pb->view(), sigma, pb->fp, pb->gpartial.p, pb->stream);
+  else
+    launch_far_grad64(pb->view(), sigma, pb->fp, pb->gpartial.p, pb->stream);
   return pb->fp;
 }
 
@@ -1280,6 +1302,20 @@ int yq_profile_read(yq_problem* pb, int32_t phase, int64_t* launches, double* to
       }
       pb->ev[phase].clear();
     }
+  });
+}
+
+int yq_fmm_stats(const yq_problem* pb, int32_t* depth, int32_t* leaves, int32_t* max_leaf,
+                 double* p2p_pairs, double* m2l_pairs) {
+  return guarded(const_cast<yq_problem*>(pb), [&] {
+    require_ready(pb);
+    YQ_REQUIRE(pb->fmm != nullptr, YQ_ESTATE, "the problem has no FMM far field");
+    const Fmm& f = *pb->fmm;
+    if (depth) *depth = f.depth;
+    if (leaves) *leaves = f.nleaf;
+    if (max_leaf) *max_leaf = f.max_leaf;
+    if (p2p_pairs) *p2p_pairs = (double)f.p2p_pairs;
+    if (m2l_pairs) *m2l_pairs = (double)f.m2l_pairs;
   });
 }
 

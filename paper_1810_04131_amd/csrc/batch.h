@@ -58,17 +58,33 @@ struct Engine {
   DevBuf<int> active, inc, jc, kc, conv;
   DevBuf<double> hb, H, cs, sn, gv, yv, scale, bnorm, rtol, res, nrm;
   DevBuf<double> V, w, r, tmp, delta, f;
-  hipGraphExec_t graph_exec[2] = {nullptr, nullptr};
+  hipGraphExec_t graph_exec[2] = {nullptr, nullptr};   // FP64, mixed iteration
+  hipGraphExec_t graph_part[6] = {};                    // the same in three parts (timers on)
+  // timers of the fused far-field launches: events around every launch and the
+  // number of source-target pairs the launches evaluated, per precision
+  bool prof_on = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev[2];
+  std::vector<hipEvent_t> ev_pool;
+  DevBuf<unsigned long long> prof_pairs;
 
   ~Engine();
   void init(const yq_params& p);
   void rebuild();
   int grid_blocks() const;
   void matvec(int prec, const int* mask, const double* Vin, const int* col, double* out);
+  void matvec_part(int part, int prec, const int* mask, const double* Vin, const int* col,
+                   double* out);
+  void iteration_part(int prec, int part);
+  void drop_graphs();
+  hipEvent_t prof_event();
+  void set_profiling(bool on);
+  void read_profile(int prec, int64_t& launches, double& ms, double& pairs, bool reset);
   void dots(const int* mask, const double* x, const double* y);
   void axpby(const int* mask, double a, const double* x, double b, const double* y, double* out);
   void iteration(int prec);
   void run_iteration(int prec);
+  // captures the iteration graphs of both precisions now (when graphs are on)
+  void ensure_graphs();
   int count_active(std::vector<int>& h);
   void solve_cycle(const int* mask, double* x);
   void clear_active(const int* mask);

@@ -43,12 +43,21 @@ constexpr int KB2 = 256;   // Krylov block size
 
 // tab: the FP64 Bessel coefficient table (the same constants for every
 // configuration), passed as an argument so that it stays in scalar registers.
+// Profiling: adds the source-target pairs of one work item (target block tb of a
+// configuration of N nodes, sources j0..j1) to the launch's counter.
+__device__ __forceinline__ void count_pairs(unsigned long long* pairs, int64_t N, int tb,
+                                            int64_t j0, int64_t j1) {
+  const int64_t nt = min((int64_t)BB, N - (int64_t)tb * BB);
+  atomicAdd(pairs, (unsigned long long)(nt * (j1 - j0)));
+}
+
 __global__ __launch_bounds__(BB) void bfar64_kernel(const ConfDev* __restrict__ cf,
                                                     const int4* __restrict__ items, int nitems,
                                                     const int* __restrict__ mask,
                                                     const double* __restrict__ V,
                                                     const int* __restrict__ col, int64_t T,
-                                                    const double* __restrict__ tab) {
+                                                    const double* __restrict__ tab,
+                                                    unsigned long long* __restrict__ pairs) {
   __shared__ double2 sxy[BB];
   __shared__ double2 sq[BB];
   const int wib = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / FG));
@@ -64,6 +73,7 @@ __global__ __launch_bounds__(BB) void bfar64_kernel(const ConfDev* __restrict__ 
     const double yi = i < N ? cd.y[i] : 0.0;
     const int64_t j0 = (int64_t)w.z * cd.chunk;
     const int64_t j1 = min(N, j0 + cd.chunk);
+    if (pairs && threadIdx.x == 0) count_pairs(pairs, N, w.y, j0, j1);
     const int64_t grp = (int64_t)w.y * (BB / FG) + wib;
     const bool live = grp * FG < N;
     double acc = 0.0;
@@ -112,7 +122,8 @@ __global__ void bpack32_kernel(const ConfDev* __restrict__ cf, const int* __rest
 // Same arithmetic as far32_kernel for each (configuration, target block, source chunk).
 __global__ __launch_bounds__(BB) void bfar32_kernel(const ConfDev* __restrict__ cf,
                                                     const int4* __restrict__ items, int nitems,
-                                                    const int* __restrict__ mask) {
+                                                    const int* __restrict__ mask,
+                                                    unsigned long long* __restrict__ pairs) {
   const int wib = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / FG));
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     const int4 w = items[it];
@@ -120,11 +131,12 @@ __global__ __launch_bounds__(BB) void bfar32_kernel(const ConfDev* __restrict__ 
     if (!mask[c]) continue;
     const ConfDev& cd = cf[c];
     const int64_t N = cd.N;
+    const int64_t j0 = (int64_t)w.z * cd.chunk;
+    const int64_t j1 = min(N, j0 + cd.chunk);
+    if (pairs && threadIdx.x == 0) count_pairs(pairs, N, w.y, j0, j1);
     const int64_t g = (int64_t)w.y * (BB / FG) + wib;
     if (g * FG >= N) continue;
     const int64_t i = (int64_t)w.y * BB + threadIdx.x;
-    const int64_t j0 = (int64_t)w.z * cd.chunk;
-    const int64_t j1 = min(N, j0 + cd.chunk);
     const float acc = far32_range(cd.f32, i, g, j0, j1);
     if (i < N) cd.part32[(int64_t)w.z * N + i] = acc;
   }
@@ -322,8 +334,13 @@ static inline unsigned nb256(int64_t n) { return (unsigned)((n + 255) / 256); }
 // ---- host engine -----------------------------------------------------------------------------
 
 Engine::~Engine() {
-  for (auto& g : graph_exec)
-    if (g) (void)hipGraphExecDestroy(g);
+  drop_graphs();
+  for (auto& v : prof_ev)
+    for (auto& e : v) {
+      (void)hipEventDestroy(e.first);
+      (void)hipEventDestroy(e.second);
+    }
+  for (auto e : ev_pool) (void)hipEventDestroy(e);
   if (own_stream && stream) (void)hipStreamDestroy(stream);
 }
 
@@ -436,11 +453,7 @@ void Engine::rebuild() {
   tmp.reserve(std::max<int64_t>(T, 1));
   delta.reserve(std::max<int64_t>(T, 1));
   f.reserve(std::max<int64_t>(T, 1));
-  for (auto& g : graph_exec)
-    if (g) {
-      (void)hipGraphExecDestroy(g);
-      g = nullptr;
-    }
+  drop_graphs();
   YQ_HIP(hipStreamSynchronize(stream));
 }
 
@@ -449,20 +462,41 @@ int Engine::grid_blocks() const {
   return std::max(1, std::min(nitems, want));
 }
 
-// out = A sigma (precision prec) for configurations in mask; input column from V/col.
-void Engine::matvec(int prec, const int* mask, const double* Vin, const int* col, double* out) {
+// The three parts of out = A sigma (precision prec) for configurations in mask,
+// input column from V/col: 0 packs the FP32 source records (mixed only), 1 the
+// fused far-field kernel, 2 the chunk sums and near correction.
+void Engine::matvec_part(int part, int prec, const int* mask, const double* Vin, const int* col,
+                         double* out) {
   if (nitems == 0) return;
-  if (prec == YQ_MIXED) {
-    bpack32_kernel<<<nb256(T), 256, 0, stream>>>(conf.p, node_conf.p, T, mask, Vin, col);
-    YQ_HIP(hipGetLastError());
-    bfar32_kernel<<<grid_blocks(), BB, 0, stream>>>(conf.p, items.p, nitems, mask);
-  } else
-    bfar64_kernel<<<grid_blocks(), BB, 0, stream>>>(conf.p, items.p, nitems, mask, Vin, col, T,
-                                                    tab64.p);
+  unsigned long long* pc = prof_on ? prof_pairs.p + (prec == YQ_MIXED ? 1 : 0) : nullptr;
+  if (part == 0) {
+    if (prec == YQ_MIXED)
+      bpack32_kernel<<<nb256(T), 256, 0, stream>>>(conf.p, node_conf.p, T, mask, Vin, col);
+  } else if (part == 1) {
+    if (prec == YQ_MIXED)
+      bfar32_kernel<<<grid_blocks(), BB, 0, stream>>>(conf.p, items.p, nitems, mask, pc);
+    else
+      bfar64_kernel<<<grid_blocks(), BB, 0, stream>>>(conf.p, items.p, nitems, mask, Vin, col, T,
+                                                      tab64.p, pc);
+  } else {
+    bfinish_kernel<<<nb256(T), 256, 0, stream>>>(conf.p, node_conf.p, T, mask, prec == YQ_MIXED,
+                                                 Vin, col, out);
+  }
   YQ_HIP(hipGetLastError());
-  bfinish_kernel<<<nb256(T), 256, 0, stream>>>(conf.p, node_conf.p, T, mask, prec == YQ_MIXED, Vin,
-                                               col, out);
-  YQ_HIP(hipGetLastError());
+}
+
+// out = A sigma; with the timers on, the far-field launch is bracketed by events.
+void Engine::matvec(int prec, const int* mask, const double* Vin, const int* col, double* out) {
+  matvec_part(0, prec, mask, Vin, col, out);
+  hipEvent_t a = prof_on ? prof_event() : nullptr;
+  if (a) YQ_HIP(hipEventRecord(a, stream));
+  matvec_part(1, prec, mask, Vin, col, out);
+  if (a) {
+    hipEvent_t b = prof_event();
+    YQ_HIP(hipEventRecord(b, stream));
+    prof_ev[prec == YQ_MIXED ? 1 : 0].push_back({a, b});
+  }
+  matvec_part(2, prec, mask, Vin, col, out);
 }
 
 // nrm[c] = x_c . y_c for masked configurations (device)
@@ -483,9 +517,19 @@ void Engine::axpby(const int* mask, double a, const double* x, double b, const d
 
 // One Arnoldi step for every active configuration (the captured sequence).
 void Engine::iteration(int prec) {
+  for (int part = 0; part < 3; ++part) iteration_part(prec, part);
+}
+
+// Parts 0 and 1 of an Arnoldi step are those of its matvec; part 2 is the rest
+// of the matvec and the orthogonalisation, Givens step and normalisation.
+void Engine::iteration_part(int prec, int part) {
+  if (part < 2) {
+    matvec_part(part, prec, active.p, V.p, jc.p, w.p);
+    return;
+  }
   const int nc = (int)members.size();
   const int hs = 2 * (m + 1) + 2;
-  matvec(prec, active.p, V.p, jc.p, w.p);
+  matvec_part(2, prec, active.p, V.p, jc.p, w.p);
   for (int pass = 0; pass < 2; ++pass) {
     bmultidot_kernel<<<nkblk, KB2, 0, stream>>>(conf.p, kblk.p, V.p, T, jc.p, w.p, active.p,
                                                 kpart.p);
@@ -505,21 +549,127 @@ void Engine::iteration(int prec) {
   YQ_HIP(hipGetLastError());
 }
 
+namespace {
+// part < 0: the whole iteration; else one of its three parts
+void capture_iteration(Engine& e, int prec, int part, hipGraphExec_t& out) {
+  hipGraph_t graph;
+  YQ_HIP(hipStreamBeginCapture(e.stream, hipStreamCaptureModeThreadLocal));
+  if (part < 0)
+    e.iteration(prec);
+  else
+    e.iteration_part(prec, part);
+  YQ_HIP(hipStreamEndCapture(e.stream, &graph));
+  YQ_HIP(hipGraphInstantiate(&out, graph, nullptr, nullptr, 0));
+  YQ_HIP(hipGraphDestroy(graph));
+}
+}  // namespace
+
+void Engine::drop_graphs() {
+  for (auto& g : graph_exec)
+    if (g) {
+      (void)hipGraphExecDestroy(g);
+      g = nullptr;
+    }
+  for (auto& g : graph_part)
+    if (g) {
+      (void)hipGraphExecDestroy(g);
+      g = nullptr;
+    }
+}
+
+void Engine::ensure_graphs() {
+  if (!use_graphs || members.empty()) return;
+  for (int gi = 0; gi < 2; ++gi) {
+    const int prec = gi ? YQ_MIXED : YQ_FP64;
+    if (!prof_on) {
+      if (!graph_exec[gi]) capture_iteration(*this, prec, -1, graph_exec[gi]);
+    } else {
+      for (int part = 0; part < 3; ++part)
+        if (!graph_part[3 * gi + part]) capture_iteration(*this, prec, part, graph_part[3 * gi + part]);
+    }
+  }
+}
+
+// One iteration: a replay of the captured graph.  With the timers on, the
+// iteration is captured as three graphs (before, the far-field kernel, after)
+// and events recorded between their launches bracket the far-field kernel.
 void Engine::run_iteration(int prec) {
   const int gi = prec == YQ_MIXED ? 1 : 0;
   if (!use_graphs) {
-    iteration(prec);
+    iteration_part(prec, 0);
+    hipEvent_t a = prof_on ? prof_event() : nullptr;
+    if (a) YQ_HIP(hipEventRecord(a, stream));
+    iteration_part(prec, 1);
+    if (a) {
+      hipEvent_t b = prof_event();
+      YQ_HIP(hipEventRecord(b, stream));
+      prof_ev[gi].push_back({a, b});
+    }
+    iteration_part(prec, 2);
     return;
   }
-  if (!graph_exec[gi]) {
-    hipGraph_t graph;
-    YQ_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
-    iteration(prec);
-    YQ_HIP(hipStreamEndCapture(stream, &graph));
-    YQ_HIP(hipGraphInstantiate(&graph_exec[gi], graph, nullptr, nullptr, 0));
-    YQ_HIP(hipGraphDestroy(graph));
+  ensure_graphs();
+  if (!prof_on) {
+    YQ_HIP(hipGraphLaunch(graph_exec[gi], stream));
+    return;
   }
-  YQ_HIP(hipGraphLaunch(graph_exec[gi], stream));
+  YQ_HIP(hipGraphLaunch(graph_part[3 * gi], stream));
+  hipEvent_t a = prof_event(), b = prof_event();
+  YQ_HIP(hipEventRecord(a, stream));
+  YQ_HIP(hipGraphLaunch(graph_part[3 * gi + 1], stream));
+  YQ_HIP(hipEventRecord(b, stream));
+  prof_ev[gi].push_back({a, b});
+  YQ_HIP(hipGraphLaunch(graph_part[3 * gi + 2], stream));
+}
+
+hipEvent_t Engine::prof_event() {
+  if (!ev_pool.empty()) {
+    hipEvent_t e = ev_pool.back();
+    ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  YQ_HIP(hipEventCreate(&e));
+  return e;
+}
+
+void Engine::set_profiling(bool on) {
+  if (on == prof_on) return;
+  YQ_HIP(hipStreamSynchronize(stream));
+  drop_graphs();   // the captured sequence changes with the timers
+  prof_on = on;
+  if (on && !prof_pairs.p) {
+    prof_pairs.alloc(2);
+    YQ_HIP(hipMemsetAsync(prof_pairs.p, 0, 2 * sizeof(unsigned long long), stream));
+    YQ_HIP(hipStreamSynchronize(stream));
+  }
+}
+
+void Engine::read_profile(int prec, int64_t& launches, double& ms, double& pairs, bool reset) {
+  const int gi = prec == YQ_MIXED ? 1 : 0;
+  YQ_HIP(hipStreamSynchronize(stream));
+  launches = (int64_t)prof_ev[gi].size();
+  ms = 0.0;
+  for (auto& e : prof_ev[gi]) {
+    float t = 0.0f;
+    YQ_HIP(hipEventElapsedTime(&t, e.first, e.second));
+    ms += t;
+  }
+  unsigned long long pc[2] = {0, 0};
+  if (prof_pairs.p)
+    YQ_HIP(hipMemcpy(pc, prof_pairs.p, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost));
+  pairs = (double)pc[gi];
+  if (reset) {
+    for (auto& e : prof_ev[gi]) {
+      ev_pool.push_back(e.first);
+      ev_pool.push_back(e.second);
+    }
+    prof_ev[gi].clear();
+    if (prof_pairs.p) {
+      YQ_HIP(hipMemsetAsync(prof_pairs.p + gi, 0, sizeof(unsigned long long), stream));
+      YQ_HIP(hipStreamSynchronize(stream));
+    }
+  }
 }
 
 // y = H^-1 g and x += V y for the masked configurations' finished cycles.

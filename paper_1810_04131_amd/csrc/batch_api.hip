@@ -12,7 +12,6 @@
 #include <memory>
 #include <numeric>
 #include <string>
-#include <thread>
 
 #include "batch.h"
 #include "common.h"
@@ -69,6 +68,12 @@ void require(const yq_batch* b) {
   YQ_REQUIRE(b->ready, YQ_ESTATE, "yq_batch_set_configs has not been called");
 }
 
+// Waits for the work queued on every FMM-lane problem's stream (every batch call
+// returns with its work done, so a later solve on a worker stream sees it).
+void sync_lane(yq_batch* b) {
+  for (int c : b->fmm_idx) YQ_HIP(hipStreamSynchronize(b->probs[c]->stream));
+}
+
 void rebuild_plans(yq_batch* b) {
   for (int c : b->direct_idx) {
     yq_problem* pb = b->probs[c].get();
@@ -93,6 +98,8 @@ int yq_batch_create(const yq_params* params, yq_batch** out) {
     yq_destroy(probe);
     YQ_REQUIRE(params->far_mode != YQ_FAR_CUTOFF, YQ_EINVAL,
                "the cutoff far field is available to single problems only");
+    YQ_REQUIRE(params->sl_coupling == 0.0, YQ_EINVAL,
+               "the combined representation (sl_coupling > 0) is available to single problems only");
     auto b = std::make_unique<yq_batch>();
     b->prm = *params;
     b->eng.init(*params);
@@ -150,6 +157,9 @@ int yq_batch_set_configs(yq_batch* b, int32_t nconf, const int32_t* np, const do
                             kappa[c]);
       YQ_REQUIRE(st == YQ_OK, st,
                  "configuration " + std::to_string(c) + ": " + yq_last_error(pb));
+      // a lane problem's set-up is queued on its own stream; it is solved later on a
+      // worker's stream, which does not order itself after that one
+      if (lane) YQ_HIP(hipStreamSynchronize(pb->stream));
       b->offsets[c + 1] = b->offsets[c] + pb->N;
       pofs += np[c];
       b->poffsets[c + 1] = pofs;
@@ -189,6 +199,7 @@ int yq_batch_boundary_label(yq_batch* b, int32_t kind, double a, double bb, doub
       int st = yq_boundary_label(b->probs[c].get(), kind, a, bb, f + b->offsets[c]);
       YQ_REQUIRE(st == YQ_OK, st, yq_last_error(b->probs[c].get()));
     }
+    sync_lane(b);
   });
 }
 
@@ -204,6 +215,7 @@ int yq_batch_set_boundary_data(yq_batch* b, const double* f) {
       YQ_REQUIRE(st == YQ_OK, st, yq_last_error(b->probs[c].get()));
     }
     YQ_HIP(hipStreamSynchronize(b->eng.stream));
+    sync_lane(b);   // the lane problems' copies of f are queued on their own streams
     b->have_f = true;
   });
 }
@@ -242,42 +254,31 @@ int yq_batch_solve(yq_batch* b, double* sigma, yq_solve_info* info) {
     std::vector<int> codes(nf, YQ_OK);
     std::vector<std::string> errs(nf);
     std::atomic<int> next{0};
-    struct Joiner {
-      std::vector<std::thread> t;
-      ~Joiner() {
-        for (auto& x : t)
-          if (x.joinable()) x.join();
-      }
-    } workers;
+    // the fused iteration's graphs are captured before any worker starts, so no
+    // capture overlaps the workers' allocations
+    if (!b->direct_idx.empty()) b->eng.ensure_graphs();
+    std::vector<std::unique_ptr<HostThread>> workers;
     for (size_t w = 0; w < b->streams.size() && nf > 0; ++w) {
-      workers.t.emplace_back([&, w] {
+      workers.push_back(std::make_unique<HostThread>([&, w] {
         (void)hipSetDevice(b->device);
         for (int k = next++; k < nf; k = next++) {
           const int c = b->fmm_idx[k];
           yq_problem* pb = b->probs[c].get();
-          pb->stream = b->streams[w];
+          pb->stream = b->streams[w];   // earlier work on its stream is done (sync_lane)
           const int st = yq_solve(pb, nullptr, sigma + b->offsets[c], &all[c]);
           codes[k] = st;
           if (st != YQ_OK && st != YQ_ENOCONV) errs[k] = yq_last_error(pb);
         }
-      });
+      }));
     }
-    // fused lane on this thread; no graph capture while the workers allocate
+    // fused lane on this thread
     if (!b->direct_idx.empty()) {
-      const bool graphs = b->eng.use_graphs;
-      if (nf > 0) b->eng.use_graphs = false;
       std::vector<yq_solve_info> inf;
-      try {
-        b->eng.solve(inf, sigma);
-        YQ_HIP(hipStreamSynchronize(b->eng.stream));
-      } catch (...) {
-        b->eng.use_graphs = graphs;
-        throw;
-      }
-      b->eng.use_graphs = graphs;
+      b->eng.solve(inf, sigma);
+      YQ_HIP(hipStreamSynchronize(b->eng.stream));
       for (size_t k = 0; k < inf.size(); ++k) all[b->direct_idx[k]] = inf[k];
     }
-    for (auto& x : workers.t) x.join();
+    for (auto& x : workers) x->join();
     for (int k = 0; k < nf; ++k)
       YQ_REQUIRE(codes[k] == YQ_OK || codes[k] == YQ_ENOCONV, codes[k],
                  "configuration " + std::to_string(b->fmm_idx[k]) + ": " + errs[k]);
@@ -315,6 +316,28 @@ int yq_batch_set_fmm(yq_batch* b, int64_t min_nodes, int32_t workers) {
     YQ_REQUIRE(!b->ready, YQ_ESTATE, "the FMM lane is set before yq_batch_set_configs");
     b->fmm_min_nodes = min_nodes;
     b->fmm_workers = workers;
+  });
+}
+
+int yq_batch_profile_enable(yq_batch* b, int32_t enable) {
+  return bguard(b, [&] {
+    YQ_REQUIRE(b, YQ_EINVAL, "null batch");
+    b->eng.set_profiling(enable != 0);
+  });
+}
+
+int yq_batch_profile_read(yq_batch* b, int32_t precision, int64_t* launches, double* total_ms,
+                          double* pairs, int32_t reset) {
+  return bguard(b, [&] {
+    YQ_REQUIRE(b && launches && total_ms && pairs, YQ_EINVAL, "null argument");
+    YQ_REQUIRE(precision == YQ_FP64 || precision == YQ_MIXED, YQ_EINVAL, "bad precision");
+    int64_t n = 0;
+    double ms = 0.0, pc = 0.0;
+    if (b->eng.prof_on || !b->eng.prof_ev[precision == YQ_MIXED ? 1 : 0].empty())
+      b->eng.read_profile(precision, n, ms, pc, reset != 0);
+    *launches = n;
+    *total_ms = ms;
+    *pairs = pc;
   });
 }
 

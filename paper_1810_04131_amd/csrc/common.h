@@ -3,7 +3,11 @@
 
 #include <hip/hip_runtime.h>
 
+#include <pthread.h>
+
 #include <cstdint>
+#include <functional>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -124,6 +128,42 @@ struct PinnedBuf {
   }
 };
 
+// A host thread with a stack of a stated size (std::thread takes the process
+// default, which can be small where a profiler's callbacks run on the same stack).
+// The constructor starts fn; join() (or the destructor) waits for it.
+class HostThread {
+ public:
+  static constexpr size_t kStack = size_t(64) << 20;
+  explicit HostThread(std::function<void()> fn) : fn_(new std::function<void()>(std::move(fn))) {
+    pthread_attr_t a;
+    pthread_attr_init(&a);
+    pthread_attr_setstacksize(&a, kStack);
+    const int rc = pthread_create(&t_, &a, &HostThread::run, fn_.get());
+    pthread_attr_destroy(&a);
+    if (rc != 0) throw Error{YQ_EDEVICE, "pthread_create failed"};
+    live_ = true;
+  }
+  HostThread(const HostThread&) = delete;
+  HostThread& operator=(const HostThread&) = delete;
+  ~HostThread() { join(); }
+  void join() {
+    if (live_) (void)pthread_join(t_, nullptr);
+    live_ = false;
+  }
+
+ private:
+  static void* run(void* f) {
+    try {
+      (*static_cast<std::function<void()>*>(f))();
+    } catch (...) {   // the callers' functions report errors through their own state
+    }
+    return nullptr;
+  }
+  std::unique_ptr<std::function<void()>> fn_;
+  pthread_t t_{};
+  bool live_ = false;
+};
+
 // Uniform loads through a constant-address-space pointer become scalar loads.
 template <class T>
 using kptr = const __attribute__((address_space(4))) T*;
@@ -155,6 +195,9 @@ struct GeomView {
   // the value sums, >= zcut_g in the gradient sums (HUGE_VAL: exact sums)
   double zcut = HUGE_VAL;
   double zcut_g = HUGE_VAL;
+  // combined representation D + eta S (eq. bwform): coupling of the single layer,
+  // 0 for the double layer alone
+  double eta = 0.0;
 };
 
 // Discretisation constants, passed to kernels by value.
@@ -239,6 +282,14 @@ void launch_finish(const GeomView& g, int win, const FarPlan& fp, const double* 
                    const double* xvals, const double* sigma, double* out, hipStream_t s);
 void launch_far_grad64(const GeomView& g, const double* sigma, const FarPlan& fp, double* partial,
                        hipStream_t s);
+// Combined representation D + g.eta S (g.eta > 0): the far field in FP64 (p64) or
+// FP32 arithmetic (p32; exactly one of the two is non-null), partials in the
+// scaling of the double-layer kernels; and its FP64 gradient.
+void launch_far_sd(const GeomView& g, const double* sigma, const FarPlan& fp, double* p64,
+                   float* p32, hipStream_t s, const int* stop = nullptr, hipEvent_t e0 = nullptr,
+                   hipEvent_t e1 = nullptr);
+void launch_far_sd_grad64(const GeomView& g, const double* sigma, const FarPlan& fp,
+                          double* partial, hipStream_t s);
 void launch_far_fused64(const GeomView& g, const double* sigma, const FarPlan& fp,
                         double* partial, double* gpartial, hipStream_t s);
 void launch_finish_grad(const GeomView& g, int win, const FarPlan& fp, const double* partial,

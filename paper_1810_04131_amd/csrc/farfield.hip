@@ -442,6 +442,142 @@ void launch_far_fused64(const GeomView& g, const double* sigma, const FarPlan& f
   YQ_HIP(hipGetLastError());
 }
 
+// ---- combined representation D + eta S (eq. bwform) ---------------------------------------
+//
+// Per pair, in the double-layer partials' scaling (finish applies kappa^2 / 2pi):
+//   (K1(z)/z) (x_i - y_j).(w nu sigma)_j + (eta / kappa^2) K0(z) (w sigma)_j,   z = kappa r,
+// since G = K0 / 2pi = (kappa^2 / 2pi) K0 / kappa^2.  Every pair takes the general
+// evaluation of K0 and K1 (both branches of bessel.h); T = float evaluates in FP32 on
+// the FP64 differences rounded to FP32.  One target per lane, 256-source tiles in LDS.
+template <typename T>
+__global__ __launch_bounds__(FAR_BS) void far_sd_kernel(GeomView g, const double* __restrict__ sigma,
+                                                        int chunk, T* __restrict__ partial,
+                                                        const int* __restrict__ stop) {
+  __shared__ double2 sxy[FAR_BS];
+  __shared__ double2 sq[FAR_BS];
+  __shared__ double sw[FAR_BS];
+  if (stop && *as_k(stop)) return;
+  const int64_t N = g.N;
+  const int64_t i = blockIdx.x * (int64_t)FAR_BS + threadIdx.x;
+  const double xi = i < N ? g.x[i] : 0.0;
+  const double yi = i < N ? g.y[i] : 0.0;
+  const double kap2 = g.kappa * g.kappa;
+  const double ek = g.eta / kap2;
+  const int64_t j0 = (int64_t)blockIdx.y * chunk;
+  const int64_t j1 = min(N, j0 + chunk);
+  T acc = 0;
+  for (int64_t jb = j0; jb < j1; jb += FAR_BS) {
+    const int64_t j = jb + threadIdx.x;
+    __syncthreads();
+    if (j < j1) {
+      const double s = sigma[j];
+      sxy[threadIdx.x] = make_double2(g.x[j], g.y[j]);
+      sq[threadIdx.x] = make_double2(g.wnx[j] * s, g.wny[j] * s);
+      sw[threadIdx.x] = ek * g.w[j] * s;
+    }
+    __syncthreads();
+    const int nb = (int)min((int64_t)FAR_BS, j1 - jb);
+    for (int k = 0; k < nb; ++k) {
+      const double2 p = sxy[k];
+      const double2 q = sq[k];
+      const double dx = xi - p.x, dy = yi - p.y;
+      if constexpr (sizeof(T) == 8) {
+        const double r2 = fma(dx, dx, dy * dy);
+        if (r2 > 0.0) {
+          double k0, k1z;
+          k0_k1z_64(kap2 * r2, k0, k1z, g.tab);
+          acc += fma(k1z, fma(dx, q.x, dy * q.y), k0 * sw[k]);
+        }
+      } else {
+        const float fx = (float)dx, fy = (float)dy;
+        const float r2 = fx * fx + fy * fy;
+        if (r2 > 0.0f) {
+          float k0, k1z;
+          k0_k1z_32((float)kap2 * r2, k0, k1z);
+          acc += k1z * (fx * (float)q.x + fy * (float)q.y) + k0 * (float)sw[k];
+        }
+      }
+    }
+  }
+  if (i < N) partial[(int64_t)blockIdx.y * N + i] = acc;
+}
+
+// Its gradient (FP64): the double layer's as in far_grad64_kernel plus
+// eta (w sigma)_j grad_x G = -(kappa^2 / 2pi) eta (w sigma)_j (K1(z)/z) (x_i - y_j).
+__global__ __launch_bounds__(FAR_BS) void far_sd_grad64_kernel(GeomView g,
+                                                               const double* __restrict__ sigma,
+                                                               int chunk,
+                                                               double* __restrict__ partial) {
+  __shared__ double2 sxy[FAR_BS];
+  __shared__ double2 sq[FAR_BS];
+  __shared__ double sw[FAR_BS];
+  const int64_t N = g.N;
+  const int64_t i = blockIdx.x * (int64_t)FAR_BS + threadIdx.x;
+  const double xi = i < N ? g.x[i] : 0.0;
+  const double yi = i < N ? g.y[i] : 0.0;
+  const double kap2 = g.kappa * g.kappa;
+  const int64_t j0 = (int64_t)blockIdx.y * chunk;
+  const int64_t j1 = min(N, j0 + chunk);
+  double ax = 0.0, ay = 0.0;
+  for (int64_t jb = j0; jb < j1; jb += FAR_BS) {
+    const int64_t j = jb + threadIdx.x;
+    __syncthreads();
+    if (j < j1) {
+      const double s = sigma[j];
+      sxy[threadIdx.x] = make_double2(g.x[j], g.y[j]);
+      sq[threadIdx.x] = make_double2(g.wnx[j] * s, g.wny[j] * s);
+      sw[threadIdx.x] = g.eta * g.w[j] * s;
+    }
+    __syncthreads();
+    const int nb = (int)min((int64_t)FAR_BS, j1 - jb);
+    for (int k = 0; k < nb; ++k) {
+      const double2 p = sxy[k];
+      const double2 q = sq[k];
+      const double dx = xi - p.x, dy = yi - p.y;
+      const double r2 = fma(dx, dx, dy * dy);
+      if (r2 > 0.0) {
+        double k0, k1z;
+        k0_k1z_64(kap2 * r2, k0, k1z, g.tab);
+        const double dq = fma(dx, q.x, dy * q.y);
+        const double b = dq * (k0 + 2.0 * k1z) * rcp64(r2) + k1z * sw[k];
+        ax += k1z * q.x - b * dx;
+        ay += k1z * q.y - b * dy;
+      }
+    }
+  }
+  if (i < N) {
+    partial[((int64_t)blockIdx.y * 2 + 0) * N + i] = ax;
+    partial[((int64_t)blockIdx.y * 2 + 1) * N + i] = ay;
+  }
+}
+
+void launch_far_sd(const GeomView& g, const double* sigma, const FarPlan& fp, double* p64,
+                   float* p32, hipStream_t s, const int* stop, hipEvent_t e0, hipEvent_t e1) {
+  YQ_REQUIRE((p64 == nullptr) != (p32 == nullptr), YQ_EINVAL, "far_sd: one partial buffer");
+  dim3 grid(fp.tblocks, fp.chunks);
+  if (p64) {
+    if (e0)
+      hipExtLaunchKernelGGL(far_sd_kernel<double>, grid, dim3(FAR_BS), 0, s, e0, e1, 0, g, sigma,
+                            fp.chunk, p64, stop);
+    else
+      far_sd_kernel<double><<<grid, FAR_BS, 0, s>>>(g, sigma, fp.chunk, p64, stop);
+  } else {
+    if (e0)
+      hipExtLaunchKernelGGL(far_sd_kernel<float>, grid, dim3(FAR_BS), 0, s, e0, e1, 0, g, sigma,
+                            fp.chunk, p32, stop);
+    else
+      far_sd_kernel<float><<<grid, FAR_BS, 0, s>>>(g, sigma, fp.chunk, p32, stop);
+  }
+  YQ_HIP(hipGetLastError());
+}
+
+void launch_far_sd_grad64(const GeomView& g, const double* sigma, const FarPlan& fp,
+                          double* partial, hipStream_t s) {
+  dim3 grid(fp.tblocks, fp.chunks);
+  far_sd_grad64_kernel<<<grid, FAR_BS, 0, s>>>(g, sigma, fp.chunk, partial);
+  YQ_HIP(hipGetLastError());
+}
+
 void launch_far_grad64(const GeomView& g, const double* sigma, const FarPlan& fp, double* partial,
                        hipStream_t s) {
   dim3 grid(fp.tblocks, fp.chunks);

@@ -10,14 +10,15 @@ namespace yq {
 struct FmmLevel {
   int nbox = 0;
   double w = 0.0;                 // box width
-  std::vector<int64_t> key;       // Morton keys (sorted)
+  int64_t off = 0;                // first box of the level in the expansion arrays
   DevBuf<double> cx, cy;          // centres
   DevBuf<int> parent;             // index at level - 1
   DevBuf<int> cpos;               // position (0..3) in the parent
   DevBuf<int> ch;                 // children indices at level + 1 [4 * nbox], -1 if empty
   DevBuf<int> ilp, ils, ilo;      // interaction list: CSR over targets, source box, offset id
   DevBuf<int> ild;                // the same as a dense table [nbox * 49] (-1: none)
-  DevBuf<double2> M, L;           // expansions [nbox * (p + 1)]
+  double2* M = nullptr;           // expansions [nbox * (p + 1)], views into Fmm::Mall / Lall
+  double2* L = nullptr;
 };
 
 struct Fmm {
@@ -27,10 +28,19 @@ struct Fmm {
   double x0 = 0.0, y0 = 0.0, W = 1.0, kappa = 1.0;
   int64_t N = 0;
   std::vector<FmmLevel> lv;       // 0..depth
+  int64_t nbox_total = 0;         // boxes of every level
+  DevBuf<double2> Mall, Lall;     // multipole and local expansions of every box, level by level
   DevBuf<int> perm;               // sorted position -> node index
   DevBuf<double> xs, ys, wnxs, wnys, qx, qy, outs;
-  DevBuf<int> leaf_start, leaf_cnt;   // per leaf box
-  DevBuf<int> nbp, nbi;               // P2P neighbour leaves (CSR, self included)
+  // leaves (boxes of any level that are not split), in node order
+  int nleaf = 0;
+  DevBuf<int> leaf_start, leaf_cnt;   // sorted-node range
+  DevBuf<int> leaf_gid;               // box index in Mall / Lall
+  DevBuf<double> leaf_cx, leaf_cy;    // box centre
+  DevBuf<int> nbp, nbi;               // P2P leaves (CSR, self included): every leaf whose
+                                      // ancestor at the coarser of the two levels is adjacent
+  int64_t p2p_pairs = 0;              // source-target pairs of one P2P pass
+  int64_t m2l_pairs = 0;              // box pairs of one M2L pass
   DevBuf<double2> tg;  // M2M / L2L tables: [level][cpos 0..3][k + 2p], k in -2p..2p
   DevBuf<double2> ts;  // M2L tables: [level][offset 0..48][k + 2p]
   int max_leaf = 0;

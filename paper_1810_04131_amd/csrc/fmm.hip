@@ -14,14 +14,17 @@
 //   L2L  L_m(c') = sum_n L_n(c) g_{n-m}(c' - c),
 //   L2P  u(x) = sum_n L_n g_n(x - c),
 // n, m = -p..p, with M_{-n} = conj(M_n), L_{-n} = conj(L_n) (real potential), so
-// only n = 0..p is stored.  Uniform quadtree over the bounding square, depth
-// chosen so that occupied leaves hold about leaf_max nodes on average;
-// interaction lists are the children of the parent's neighbours that are not
-// adjacent; leaves interact directly with their 3 x 3 neighbourhood (P2P uses
-// the far-field kernels' pair formula, so the QBX correction still cancels the
-// plain terms of window pairs).  Tree and lists are built on the host once per
-// geometry; translation tables (per level, child position or offset) on the
-// device.
+// only n = 0..p is stored.  Quadtree over the bounding square, uniform down to the
+// level where occupied boxes average leaf_max nodes and adaptive below it (a box
+// over leaf_max is split further), so leaves sit on different levels and hold at
+// most leaf_max nodes (quadtree.h); interaction lists are the children of the parent's
+// neighbours that are not adjacent; a leaf interacts directly with every leaf
+// whose ancestor at the coarser of the two levels is adjacent to its own (P2P
+// uses the far-field kernels' pair formula, so the QBX correction still cancels
+// the plain terms of window pairs).  Tree and lists are built on the host once
+// per geometry; translation tables (per level, child position or offset) on the
+// device.  The expansions of all levels live in one array each (Mall, Lall), so
+// a leaf's coefficients are addressed by its box index there.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -36,6 +39,7 @@
 #include "common.h"
 #include "farfield_core.h"
 #include "fmm.h"
+#include "quadtree.h"
 
 namespace yq {
 
@@ -193,10 +197,12 @@ constexpr int FB = 64;
 
 // One wave per leaf: multipole coefficients M_n, n = 0..p.  A lane takes one
 // node at a time, rolls I_{n-1}, I_n, I_{n+1} and e^{i(n +- 1) phi} along n, and
-// the wave sums each coefficient; lane n keeps M_n.
+// the wave sums each coefficient; lane n keeps M_n.  Leaf b's coefficients go to
+// box gid[b] of M.
 __global__ __launch_bounds__(64) void p2m_kernel(int p, int use_col, double kappa,
                                                  const int* __restrict__ ls,
                                                  const int* __restrict__ lc,
+                                                 const int* __restrict__ gid,
                                                  const double* __restrict__ ccx,
                                                  const double* __restrict__ ccy,
                                                  const double* __restrict__ xs,
@@ -254,7 +260,7 @@ __global__ __launch_bounds__(64) void p2m_kernel(int p, int use_col, double kapp
   }
   if (lane <= p) {
     const double sc = kappa / (4.0 * PI);
-    M[(int64_t)b * (p + 1) + lane] = make_double2(mine.x * sc, mine.y * sc);
+    M[(int64_t)gid[b] * (p + 1) + lane] = make_double2(mine.x * sc, mine.y * sc);
   }
 }
 
@@ -265,6 +271,8 @@ __global__ void m2m_kernel(int p, int nbox, const int* __restrict__ ch, const do
   if (t >= (int64_t)nbox * (p + 1)) return;
   const int P = (int)(t / (p + 1)), n = (int)(t % (p + 1));
   const int K = 4 * p + 1;
+  // a leaf keeps the coefficients of its own nodes (P2M)
+  if (ch[4 * P] < 0 && ch[4 * P + 1] < 0 && ch[4 * P + 2] < 0 && ch[4 * P + 3] < 0) return;
   double2 sum = make_double2(0.0, 0.0);
   for (int pos = 0; pos < 4; ++pos) {
     const int c = ch[4 * P + pos];
@@ -580,7 +588,10 @@ __global__ __launch_bounds__(256) void tree_mfma_kernel(int p, int nbox, const i
     tile_load<KS>(op, A, c >= 0 ? X + (int64_t)c * P1 : nullptr, P1, kk);
     dbl4 acc = tile_mfma<KS>(op, dbl4{0.0, 0.0, 0.0, 0.0});
     acc = block_tile_sum(acc, red);
-    if (pos == 0 && tb < nbox) tile_store<false>(Y + (int64_t)tb * P1, rt, kk, P1, acc);
+    // a leaf keeps the coefficients of its own nodes (P2M)
+    const bool split = tb < nbox && (ch[4 * (int64_t)tb] >= 0 || ch[4 * (int64_t)tb + 1] >= 0 ||
+                                     ch[4 * (int64_t)tb + 2] >= 0 || ch[4 * (int64_t)tb + 3] >= 0);
+    if (pos == 0 && split) tile_store<false>(Y + (int64_t)tb * P1, rt, kk, P1, acc);
   } else {
     if (__ballot(c >= 0) == 0) return;          // whole wave: no child at this position
     tile_load<KS>(op, A, tb < nbox ? X + (int64_t)tb * P1 : nullptr, P1, kk);
@@ -608,12 +619,13 @@ __global__ void l2l_kernel(int p, int nbox, const int* __restrict__ parent, cons
 }
 
 // Waves per leaf in l2p_p2p_grad_kernel (and l2p_p2p_kernel below kLeavesFor2): wave
-// w takes every PW-th neighbour leaf of the 3 x 3 neighbourhood (a leaf holds at most
-// 64 targets, so one wave per leaf left most SIMDs with a single wave to hide latency);
-// the waves' partial sums are combined in a fixed order by wave 0, which also
-// evaluates the local expansion.  From kLeavesFor2 leaves on the leaves alone fill the
-// SIMDs and l2p_p2p_kernel takes two waves per leaf (measured: 4 waves best at 800
-// leaves, 2 at 4,000; 8 slower at both).
+// w takes every PW-th leaf of the leaf's P2P list (a leaf holds at most leaf_max
+// targets, 64 by default, so one wave per leaf left most SIMDs with a single wave to
+// hide latency); the waves' partial sums are combined in a fixed order by wave 0,
+// which also evaluates the local expansion.  From kLeavesFor2 leaves on the leaves
+// alone fill the SIMDs and l2p_p2p_kernel takes two waves per leaf (measured on the
+// uniform tree this replaced: 4 waves best at 800 leaves, 2 at 4,000; 8 slower at
+// both).
 constexpr int PW = 4;
 constexpr int kLeavesFor2 = 2048;
 
@@ -625,12 +637,13 @@ __device__ __forceinline__ void wave_sync() {
 }
 
 // One block per leaf: local expansion at the leaf's targets plus the direct
-// interactions with the 3 x 3 neighbourhood; writes partial[node] in the far-field
-// kernels' scaling (far field * 2 pi / kappa^2).
+// interactions with the leaves of its P2P list; writes partial[node] in the
+// far-field kernels' scaling (far field * 2 pi / kappa^2).
 template <bool F32, int NW>
 __global__ __launch_bounds__(FB * NW) void l2p_p2p_kernel(int p, double kappa, int use_local, int use_col,
                                                           const int* __restrict__ ls,
                                                           const int* __restrict__ lc,
+                                                          const int* __restrict__ gid,
                                                           const int* __restrict__ nbp,
                                                           const int* __restrict__ nbi,
                                                           const double* __restrict__ ccx,
@@ -696,7 +709,7 @@ __global__ __launch_bounds__(FB * NW) void l2p_p2p_kernel(int p, double kappa, i
         const double rho = sqrt(dx * dx + dy * dy);
         const double x = kappa * rho, t = 0.25 * x * x, hx = 0.5 * x;
         const double2 e1 = rho > 0.0 ? make_double2(dx / rho, dy / rho) : make_double2(1.0, 0.0);
-        const double2* lb = L + (int64_t)b * (p + 1);
+        const double2* lb = L + (int64_t)gid[b] * (p + 1);
         if (use_col) iscaled_col(t, p, col);
         loc = lb[0].x * (use_col ? col[0] : iorder(t, 1.0, 0));
         double2 E = e1;
@@ -715,7 +728,7 @@ __global__ __launch_bounds__(FB * NW) void l2p_p2p_kernel(int p, double kappa, i
 }
 
 // Gradient counterpart of l2p_p2p_kernel (FP64): the direct gradient from the
-// 3 x 3 neighbourhood plus the local expansion's gradient
+// leaves of the P2P list plus the local expansion's gradient
 //   u_x + i u_y = kappa [ L_0 I_1 e^{i theta}
 //                 + sum_{n>=1} (L_n I_{n+1} e^{i(n+1) theta} + conj(L_n) I_{n-1} e^{-i(n-1) theta}) ],
 // since (d/dx + i d/dy) I_n(kappa rho) e^{i n theta} = kappa I_{n+1} e^{i(n+1) theta} for
@@ -724,6 +737,7 @@ __global__ __launch_bounds__(FB * NW) void l2p_p2p_kernel(int p, double kappa, i
 __global__ __launch_bounds__(FB * PW) void l2p_p2p_grad_kernel(int p, int use_col, double kappa,
                                                           const int* __restrict__ ls,
                                                           const int* __restrict__ lc,
+                                                          const int* __restrict__ gid,
                                                           const int* __restrict__ nbp,
                                                           const int* __restrict__ nbi,
                                                           const double* __restrict__ ccx,
@@ -780,7 +794,7 @@ __global__ __launch_bounds__(FB * PW) void l2p_p2p_grad_kernel(int p, int use_co
       const double rho = sqrt(dx * dx + dy * dy);
       const double x = kappa * rho, t = 0.25 * x * x, hx = 0.5 * x;
       const double2 e1 = rho > 0.0 ? make_double2(dx / rho, dy / rho) : make_double2(1.0, 0.0);
-      const double2* lb = L + (int64_t)b * (p + 1);
+      const double2* lb = L + (int64_t)gid[b] * (p + 1);
       if (use_col) iscaled_col(t, p + 1, col);
       double pref = hx;                                   // (x/2)^{n+1} / (n+1)!
       double Iprev = use_col ? col[0] : iorder(t, 1.0, 0);        // I_{n-1}
@@ -892,33 +906,6 @@ __global__ void sort_gather_kernel(int64_t n, const int* __restrict__ perm,
 
 // ---- host --------------------------------------------------------------------------------
 
-// Bit interleaving for Morton keys (x in the even bits), grid coordinates < 2^31.
-static inline uint64_t spread_bits(uint64_t v) {
-  v &= 0x7fffffffULL;
-  v = (v | (v << 16)) & 0x0000ffff0000ffffULL;
-  v = (v | (v << 8)) & 0x00ff00ff00ff00ffULL;
-  v = (v | (v << 4)) & 0x0f0f0f0f0f0f0f0fULL;
-  v = (v | (v << 2)) & 0x3333333333333333ULL;
-  v = (v | (v << 1)) & 0x5555555555555555ULL;
-  return v;
-}
-static inline uint64_t gather_bits(uint64_t v) {
-  v &= 0x5555555555555555ULL;
-  v = (v | (v >> 1)) & 0x3333333333333333ULL;
-  v = (v | (v >> 2)) & 0x0f0f0f0f0f0f0f0fULL;
-  v = (v | (v >> 4)) & 0x00ff00ff00ff00ffULL;
-  v = (v | (v >> 8)) & 0x0000ffff0000ffffULL;
-  v = (v | (v >> 16)) & 0x00000000ffffffffULL;
-  return v;
-}
-static inline int64_t morton(int64_t ix, int64_t iy) {
-  return (int64_t)(spread_bits((uint64_t)ix) | (spread_bits((uint64_t)iy) << 1));
-}
-static inline void unmorton(int64_t k, int64_t& ix, int64_t& iy) {
-  ix = (int64_t)gather_bits((uint64_t)k);
-  iy = (int64_t)gather_bits((uint64_t)k >> 1);
-}
-
 // Host-to-device uploads during set-up: each array is kept until finish(), which
 // packs them into the pinned staging buffer, issues one asynchronous copy per
 // array and waits for the stream.  Device buffers only grow (DevBuf::fit).
@@ -992,32 +979,6 @@ struct Uploader {
   }
 };
 
-// Lookup of occupied boxes by grid position at one level: a dense table while the
-// level's grid is small, a hash map above that.
-struct BoxIndex {
-  int l = 0;
-  std::vector<int> dense;
-  std::unordered_map<int64_t, int> sparse;
-  void init(int level, const std::vector<int64_t>& keys) {
-    l = level;
-    const int64_t cells = 1LL << (2 * level);
-    dense.clear();
-    sparse.clear();
-    if (cells <= (1LL << 24)) {
-      dense.assign((size_t)cells, -1);
-      for (size_t b = 0; b < keys.size(); ++b) dense[(size_t)keys[b]] = (int)b;
-    } else {
-      sparse.reserve(keys.size() * 2);
-      for (size_t b = 0; b < keys.size(); ++b) sparse[keys[b]] = (int)b;
-    }
-  }
-  int find(int64_t key) const {
-    if (!dense.empty()) return key >= 0 && key < (int64_t)dense.size() ? dense[(size_t)key] : -1;
-    auto it = sparse.find(key);
-    return it == sparse.end() ? -1 : it->second;
-  }
-};
-
 Fmm::~Fmm() {
   if (dn_done) (void)hipEventDestroy(dn_done);
 }
@@ -1069,146 +1030,84 @@ void Fmm::build(int64_t n, double kap, int order, int lmax, const double* tab, h
   YQ_HIP(hipEventSynchronize(dn_done));
   root_box(reinterpret_cast<const double*>(stage_dn.p), W, x0, y0);
   const uint32_t* skey = reinterpret_cast<const uint32_t*>(stage_dn.p + 4 * sizeof(double));
-  // Depth: occupied boxes per level in one pass over the sorted keys.  Sorted
-  // neighbours k-1, k fall in different boxes at level d exactly when the
-  // highest differing bit of their keys is at or above bit 2 (DMAX - d), i.e.
-  // from level DMAX - msb/2 on.
+  // Uniform down to the first level (>= 2) where the occupied boxes hold leaf_max
+  // nodes or fewer on average, adaptive below it: boxes still over leaf_max keep
+  // splitting.  (Sorted neighbours k-1, k fall in different boxes at level d exactly
+  // when the highest differing bit of their keys is at or above bit 2 (DMAX - d).)
+  // Splitting top-down from the root alone leaves large sparse leaves beside the
+  // particles' boundary curves, whose direct lists then take whole subtrees of
+  // their split neighbours: twice the direct pairs of this tree on the
+  // 500-ellipse workload.
+  int base = DMAX;
   {
     std::vector<int64_t> first(DMAX + 2, 0);
     for (int64_t k = 1; k < n; ++k) {
       const uint32_t x = skey[k] ^ skey[k - 1];
       if (!x) continue;
-      const int msb = 31 - __builtin_clz(x);
-      ++first[DMAX - msb / 2];
+      ++first[DMAX - (31 - __builtin_clz(x)) / 2];
     }
-    depth = DMAX;
     int64_t occ = 1;
     for (int d = 0; d <= DMAX; ++d) {
       occ += first[d];
       if (d >= 2 && (double)n / occ <= (double)leaf_max) {
-        depth = d;
+        base = d;
         break;
       }
     }
   }
-  const int shl = 2 * (DMAX - depth);
+  const qt::Tree t = qt::build(skey, n, DMAX, leaf_max, base);
+  depth = t.depth;
+  max_leaf = t.max_leaf;
+  p2p_pairs = t.p2p_pairs;
   lv.resize(depth + 1);   // levels keep their device buffers from earlier builds
-  for (auto& L : lv) L.key.clear();
-  std::vector<int> hls, hlc;
-  {
-    FmmLevel& L = lv[depth];
-    for (int64_t k = 0; k < n; ++k) {
-      const int64_t kk = (int64_t)(skey[k] >> shl);
-      if (L.key.empty() || L.key.back() != kk) {
-        L.key.push_back(kk);
-        hls.push_back((int)k);
-        hlc.push_back(0);
-      }
-      ++hlc.back();
-    }
-  }
-  // parents: level l - 1 holds the distinct (key >> 2) of level l, in order
-  std::vector<std::vector<int>> par(depth + 1);
-  for (int l = depth; l >= 1; --l) {
-    std::vector<int64_t>& ck = lv[l].key;
-    std::vector<int64_t>& pk = lv[l - 1].key;
-    par[l].resize(ck.size());
-    for (size_t b = 0; b < ck.size(); ++b) {
-      if (pk.empty() || pk.back() != (ck[b] >> 2)) pk.push_back(ck[b] >> 2);
-      par[l][b] = (int)pk.size() - 1;
-    }
-  }
-  max_leaf = *std::max_element(hlc.begin(), hlc.end());
-  // per level: grid coordinates, children, colleagues (the <= 9 adjacent boxes of
-  // the same level, the box itself included, in (dx, dy) order, -1 where none)
-  std::vector<std::vector<int>> bx(depth + 1), by(depth + 1), chl(depth + 1), col(depth + 1);
+  nbox_total = 0;
+  m2l_pairs = 0;
   for (int l = 0; l <= depth; ++l) {
+    const qt::Level& T = t.lv[l];
     FmmLevel& L = lv[l];
-    L.nbox = (int)L.key.size();
+    L.nbox = T.nbox();
     L.w = W / (double)(1LL << l);
-    bx[l].resize(L.nbox);
-    by[l].resize(L.nbox);
-    for (int b = 0; b < L.nbox; ++b) {
-      int64_t ix, iy;
-      unmorton(L.key[b], ix, iy);
-      bx[l][b] = (int)ix;
-      by[l][b] = (int)iy;
-    }
-    chl[l].assign(4 * (size_t)L.nbox, -1);
-  }
-  for (int l = 1; l <= depth; ++l)
-    for (int c = 0; c < lv[l].nbox; ++c) chl[l - 1][4 * (size_t)par[l][c] + (lv[l].key[c] & 3)] = c;
-  for (int l = 0; l <= depth; ++l) {
-    BoxIndex idx;
-    idx.init(l, lv[l].key);
-    const int64_t lim = 1LL << l;
-    col[l].assign(9 * (size_t)lv[l].nbox, -1);
-    for (int b = 0; b < lv[l].nbox; ++b)
-      for (int ddx = -1; ddx <= 1; ++ddx)
-        for (int ddy = -1; ddy <= 1; ++ddy) {
-          const int64_t qx_ = bx[l][b] + ddx, qy_ = by[l][b] + ddy;
-          if (qx_ < 0 || qy_ < 0 || qx_ >= lim || qy_ >= lim) continue;
-          col[l][9 * (size_t)b + (ddx + 1) * 3 + (ddy + 1)] = idx.find(morton(qx_, qy_));
-        }
-  }
-  std::vector<int> hnbp(1, 0), hnbi;
-  for (int l = 0; l <= depth; ++l) {
-    FmmLevel& L = lv[l];
+    L.off = nbox_total;
+    nbox_total += L.nbox;
     std::vector<double> hcx(L.nbox), hcy(L.nbox);
-    std::vector<int> hpar(L.nbox, -1), hpos(L.nbox, 0);
-    std::vector<int> ilp(1, 0), ils, ilo;
     for (int b = 0; b < L.nbox; ++b) {
-      const int ix = bx[l][b], iy = by[l][b];
-      hcx[b] = x0 + (ix + 0.5) * L.w;
-      hcy[b] = y0 + (iy + 0.5) * L.w;
-      if (l > 0) {
-        hpar[b] = par[l][b];
-        hpos[b] = (int)(L.key[b] & 3);
-      }
-      if (l >= 2) {
-        // interaction list: children of the parent's colleagues that are not
-        // adjacent to the box
-        const int* pc = &col[l - 1][9 * (size_t)par[l][b]];
-        for (int e = 0; e < 9; ++e) {
-          if (pc[e] < 0) continue;
-          for (int pos = 0; pos < 4; ++pos) {
-            const int sb = chl[l - 1][4 * (size_t)pc[e] + pos];
-            if (sb < 0) continue;
-            const int ox = bx[l][sb] - ix, oy = by[l][sb] - iy;
-            if (std::abs(ox) <= 1 && std::abs(oy) <= 1) continue;
-            ils.push_back(sb);
-            ilo.push_back((ox + 3) * 7 + (oy + 3));
-          }
-        }
-        ilp.push_back((int)ils.size());
-      }
-      if (l == depth) {
-        for (int e = 0; e < 9; ++e) {
-          const int nb = col[l][9 * (size_t)b + e];
-          if (nb >= 0) hnbi.push_back(nb);
-        }
-        hnbp.push_back((int)hnbi.size());
-      }
+      hcx[b] = x0 + (T.ix[b] + 0.5) * L.w;
+      hcy[b] = y0 + (T.iy[b] + 0.5) * L.w;
     }
+    std::vector<int> hpar(T.parent), hpos(T.cpos);
+    if (l == 0) hpar[0] = -1;
     up(L.cx, hcx);
     up(L.cy, hcy);
     up(L.parent, hpar);
     up(L.cpos, hpos);
-    up(L.ch, chl[l]);
+    up(L.ch, T.child);
     if (l >= 2) {
-      up(L.ilp, ilp);
-      up(L.ils, ils);
-      up(L.ilo, ilo);
+      up(L.ilp, T.ilp);
+      up(L.ils, T.ils);
+      up(L.ilo, T.ilo);
       std::vector<int> dense((size_t)L.nbox * 49, -1);
       for (int b = 0; b < L.nbox; ++b)
-        for (int e = ilp[b]; e < ilp[b + 1]; ++e) dense[(size_t)b * 49 + ilo[e]] = ils[e];
+        for (int e = T.ilp[b]; e < T.ilp[b + 1]; ++e) dense[(size_t)b * 49 + T.ilo[e]] = T.ils[e];
       up(L.ild, dense);
+      m2l_pairs += (int64_t)T.ils.size();
     }
   }
-  up(leaf_start, hls);
-  up(leaf_cnt, hlc);
-  up(nbp, hnbp);
-  up(nbi, hnbi);
+  nleaf = (int)t.leaf_level.size();
+  std::vector<int> gid(nleaf);
+  std::vector<double> lcx(nleaf), lcy(nleaf);
+  for (int k = 0; k < nleaf; ++k) {
+    const int l = t.leaf_level[k], b = t.leaf_box[k];
+    gid[k] = (int)(lv[l].off + b);
+    lcx[k] = x0 + (t.lv[l].ix[b] + 0.5) * lv[l].w;
+    lcy[k] = y0 + (t.lv[l].iy[b] + 0.5) * lv[l].w;
+  }
+  up(leaf_start, t.leaf_start);
+  up(leaf_cnt, t.leaf_cnt);
+  up(leaf_gid, gid);
+  up(leaf_cx, lcx);
+  up(leaf_cy, lcy);
+  up(nbp, t.nbp);
+  up(nbi, t.nbi);
   qx.fit(n);
   qy.fit(n);
   up.finish();
@@ -1219,9 +1118,11 @@ void Fmm::build(int64_t n, double kap, int order, int lmax, const double* tab, h
 void Fmm::set_order(int q, const double* tab, hipStream_t s) {
   YQ_REQUIRE(q >= 1 && q <= MAXP_FMM, YQ_EINVAL, "FMM order must be in 1..48");
   p = q;
+  Mall.fit((size_t)std::max<int64_t>(nbox_total, 1) * (p + 1));
+  Lall.fit((size_t)std::max<int64_t>(nbox_total, 1) * (p + 1));
   for (auto& L : lv) {
-    L.M.fit((size_t)std::max(L.nbox, 1) * (p + 1));
-    L.L.fit((size_t)std::max(L.nbox, 1) * (p + 1));
+    L.M = Mall.p + L.off * (p + 1);
+    L.L = Lall.p + L.off * (p + 1);
   }
   const int K = 4 * p + 1;
   tg.fit((size_t)(depth + 1) * 4 * K);
@@ -1287,11 +1188,15 @@ void Fmm::copy_tree(const Fmm& o, int q, const double* tab, hipStream_t s) {
   kappa = o.kappa;
   N = o.N;
   max_leaf = o.max_leaf;
+  nbox_total = o.nbox_total;
+  nleaf = o.nleaf;
+  p2p_pairs = o.p2p_pairs;
+  m2l_pairs = o.m2l_pairs;
   lv.resize(o.lv.size());
   for (size_t l = 0; l < o.lv.size(); ++l) {
     lv[l].nbox = o.lv[l].nbox;
     lv[l].w = o.lv[l].w;
-    lv[l].key = o.lv[l].key;
+    lv[l].off = o.lv[l].off;
     dup(lv[l].cx, o.lv[l].cx);
     dup(lv[l].cy, o.lv[l].cy);
     dup(lv[l].parent, o.lv[l].parent);
@@ -1311,6 +1216,9 @@ void Fmm::copy_tree(const Fmm& o, int q, const double* tab, hipStream_t s) {
   dup(wnys, o.wnys);
   dup(leaf_start, o.leaf_start);
   dup(leaf_cnt, o.leaf_cnt);
+  dup(leaf_gid, o.leaf_gid);
+  dup(leaf_cx, o.leaf_cx);
+  dup(leaf_cy, o.leaf_cy);
   dup(nbp, o.nbp);
   dup(nbi, o.nbi);
   if (!cp.empty()) {
@@ -1333,8 +1241,8 @@ void Fmm::m2l_mfma(hipStream_t s, const int* stop) {
   M2LLevels a{};
   for (int l = 2; l <= depth; ++l) {
     a.ild[l] = lv[l].ild.p;
-    a.M[l] = lv[l].M.p;
-    a.L[l] = lv[l].L.p;
+    a.M[l] = lv[l].M;
+    a.L[l] = lv[l].L;
     a.nbox[l] = lv[l].nbox;
   }
   const int RT = R16 / 16;
@@ -1357,8 +1265,8 @@ void Fmm::m2l_mfma32(hipStream_t s, const int* stop) {
   M2LLevels a{};
   for (int l = 2; l <= depth; ++l) {
     a.ild[l] = lv[l].ild.p;
-    a.M[l] = lv[l].M.p;
-    a.L[l] = lv[l].L.p;
+    a.M[l] = lv[l].M;
+    a.L[l] = lv[l].L;
     a.nbox[l] = lv[l].nbox;
   }
   const int RT = R16 / 16;
@@ -1385,8 +1293,8 @@ void Fmm::tree_mfma(bool gather, int l, hipStream_t s) {
   const int RT = R16 / 16;
   const unsigned g = (unsigned)(((nb + 15) / 16) * RT);   // one block per (tile, row tile)
   const double* A = gmat.p + (size_t)(l + 1) * 4 * R16 * R16;
-  const double2* X = gather ? lv[l + 1].M.p : lv[l].L.p;
-  double2* Y = gather ? lv[l].M.p : lv[l + 1].L.p;
+  const double2* X = gather ? lv[l + 1].M : lv[l].L;
+  double2* Y = gather ? lv[l].M : lv[l + 1].L;
   const int* ch = lv[l].ch.p;
 #define YQ_TREE(rt)                                                                  \
   if (gather)                                                                        \
@@ -1413,19 +1321,19 @@ void Fmm::expansions(const double* sigma, hipStream_t s, bool m2l32, const int* 
   const int K = 4 * p + 1;
   gather_kernel<<<(unsigned)((N + 255) / 256), 256, 0, s>>>(N, perm.p, sigma, wnxs.p, wnys.p, qx.p,
                                                             qy.p);
-  FmmLevel& leaf = lv[depth];
   const int col = p <= kColMaxOrder;
-  p2m_kernel<<<leaf.nbox, 64, col ? (size_t)(p + 2) * 64 * sizeof(double) : 0, s>>>(p, col, kappa, leaf_start.p, leaf_cnt.p, leaf.cx.p, leaf.cy.p, xs.p,
-                                      ys.p, qx.p, qy.p, leaf.M.p, stop);
+  p2m_kernel<<<nleaf, 64, col ? (size_t)(p + 2) * 64 * sizeof(double) : 0, s>>>(
+      p, col, kappa, leaf_start.p, leaf_cnt.p, leaf_gid.p, leaf_cx.p, leaf_cy.p, xs.p, ys.p, qx.p,
+      qy.p, Mall.p, stop);
   for (int l = depth - 1; l >= 2; --l) {
     if (use_mfma) {
       tree_mfma(true, l, s);
       continue;
     }
     const int64_t nt = (int64_t)lv[l].nbox * (p + 1);
-    m2m_kernel<<<(unsigned)((nt + 127) / 128), 128, 0, s>>>(p, lv[l].nbox, lv[l].ch.p, lv[l + 1].M.p,
+    m2m_kernel<<<(unsigned)((nt + 127) / 128), 128, 0, s>>>(p, lv[l].nbox, lv[l].ch.p, lv[l + 1].M,
                                                             tg.p + (size_t)(l + 1) * 4 * K,
-                                                            lv[l].M.p);
+                                                            lv[l].M);
   }
   if (use_mfma && m2l32) {
     m2l_mfma32(s, stop);
@@ -1435,8 +1343,8 @@ void Fmm::expansions(const double* sigma, hipStream_t s, bool m2l32, const int* 
     for (int l = 2; l <= depth; ++l) {
       const int64_t nt = (int64_t)lv[l].nbox * (p + 1);
       m2l_kernel<<<(unsigned)((nt + 127) / 128), 128, 0, s>>>(p, lv[l].nbox, lv[l].ilp.p, lv[l].ils.p,
-                                                              lv[l].ilo.p, lv[l].M.p,
-                                                              ts.p + (size_t)l * 49 * K, lv[l].L.p);
+                                                              lv[l].ilo.p, lv[l].M,
+                                                              ts.p + (size_t)l * 49 * K, lv[l].L);
     }
   }
   for (int l = 2; l < depth; ++l) {
@@ -1446,9 +1354,9 @@ void Fmm::expansions(const double* sigma, hipStream_t s, bool m2l32, const int* 
     }
     const int64_t nt = (int64_t)lv[l + 1].nbox * (p + 1);
     l2l_kernel<<<(unsigned)((nt + 127) / 128), 128, 0, s>>>(p, lv[l + 1].nbox, lv[l + 1].parent.p,
-                                                            lv[l + 1].cpos.p, lv[l].L.p,
+                                                            lv[l + 1].cpos.p, lv[l].L,
                                                             tg.p + (size_t)(l + 1) * 4 * K,
-                                                            lv[l + 1].L.p);
+                                                            lv[l + 1].L);
   }
 }
 
@@ -1456,28 +1364,27 @@ void Fmm::apply(const double* sigma, double* partial, bool p2p_fp32, const doubl
                 hipStream_t s, const int* stop) {
   // the FP32-class (inner) operator also takes its M2L in FP32 when that is set up
   expansions(sigma, s, p2p_fp32 && want_m2l32 && use_mfma, stop);
-  FmmLevel& leaf = lv[depth];
   const int col = p <= kColMaxOrder;
-  const int nw = leaf.nbox >= kLeavesFor2 ? 2 : PW;
+  const int nw = nleaf >= kLeavesFor2 ? 2 : PW;
   const size_t sh_l = (size_t)nw * FB * (2 * sizeof(double2) + sizeof(float2) + sizeof(double)) +
                       (col ? (size_t)(p + 1) * 64 * sizeof(double) : 0);
   auto k = p2p_fp32 ? (nw == 2 ? l2p_p2p_kernel<true, 2> : l2p_p2p_kernel<true, PW>)
                     : (nw == 2 ? l2p_p2p_kernel<false, 2> : l2p_p2p_kernel<false, PW>);
-  k<<<leaf.nbox, FB * nw, sh_l, s>>>(p, kappa, 1, col, leaf_start.p, leaf_cnt.p, nbp.p, nbi.p,
-                                     leaf.cx.p, leaf.cy.p, leaf.L.p, xs.p, ys.p, qx.p, qy.p, perm.p,
-                                     tab, partial, stop);
+  k<<<nleaf, FB * nw, sh_l, s>>>(p, kappa, 1, col, leaf_start.p, leaf_cnt.p, leaf_gid.p, nbp.p,
+                                 nbi.p, leaf_cx.p, leaf_cy.p, Lall.p, xs.p, ys.p, qx.p, qy.p,
+                                 perm.p, tab, partial, stop);
   YQ_HIP(hipGetLastError());
 }
 
 void Fmm::apply_grad(const double* sigma, double* gpart, const double* tab, hipStream_t s) {
   expansions(sigma, s);
-  FmmLevel& leaf = lv[depth];
   const int col = p <= kColMaxOrder;
   const size_t sh =
       (size_t)PW * FB * 3 * sizeof(double2) + (col ? (size_t)(p + 2) * 64 * sizeof(double) : 0);
-  l2p_p2p_grad_kernel<<<leaf.nbox, FB * PW, sh, s>>>(p, col, kappa, leaf_start.p, leaf_cnt.p, nbp.p,
-                                                      nbi.p, leaf.cx.p, leaf.cy.p, leaf.L.p, xs.p,
-                                                      ys.p, qx.p, qy.p, perm.p, N, tab, gpart);
+  l2p_p2p_grad_kernel<<<nleaf, FB * PW, sh, s>>>(p, col, kappa, leaf_start.p, leaf_cnt.p,
+                                                  leaf_gid.p, nbp.p, nbi.p, leaf_cx.p, leaf_cy.p,
+                                                  Lall.p, xs.p, ys.p, qx.p, qy.p, perm.p, N, tab,
+                                                  gpart);
   YQ_HIP(hipGetLastError());
 }
 

@@ -144,7 +144,10 @@ __global__ __launch_bounds__(64) void potential_kernel(GeomView g, PotFine pf, d
   const int64_t J1 = min(npan, J0 + per);
   const int F = pf.nsub * Q;
   kptr<double> sx = as_k(g.x), sy = as_k(g.y), swx = as_k(g.wnx), swy = as_k(g.wny);
-  kptr<double> ssg = as_k(sigma);
+  kptr<double> ssg = as_k(sigma), sww = as_k(g.w);
+  // combined representation D + eta S: the single layer's eta w G, in the same
+  // kappa^2 / 2pi scaling (G = (kappa^2 / 2pi) K0 / kappa^2)
+  const double ek = g.eta / kap2;
   double acc = 0.0;
   for (int64_t J = J0; J < J1; ++J) {
     const int64_t b = J * Q;
@@ -153,7 +156,13 @@ __global__ __launch_bounds__(64) void potential_kernel(GeomView g, PotFine pf, d
       const double dx = zx - sx[b + m], dy = zy - sy[b + m];
       const double r2 = dx * dx + dy * dy;
       d2 = fmin(d2, r2);
-      part += k1z_64(kap2 * r2, g.tab) * (dx * swx[b + m] + dy * swy[b + m]) * ssg[b + m];
+      if (g.eta > 0.0) {
+        double k0, k1z;
+        k0_k1z_64(kap2 * r2, k0, k1z, g.tab);
+        part += (k1z * (dx * swx[b + m] + dy * swy[b + m]) + ek * k0 * sww[b + m]) * ssg[b + m];
+      } else {
+        part += k1z_64(kap2 * r2, g.tab) * (dx * swx[b + m] + dy * swy[b + m]) * ssg[b + m];
+      }
     }
     const double bh = beta * g.panel_h[J];
     const bool near = active && d2 < bh * bh;
@@ -173,7 +182,14 @@ __global__ __launch_bounds__(64) void potential_kernel(GeomView g, PotFine pf, d
       double sum = 0.0;
       for (int k = lane; k < F; k += 64) {
         const double dx = ux - fx[k], dy = uy - fy[k];
-        sum += k1z_64(kap2 * (dx * dx + dy * dy), g.tab) * (dx * fwx[k] + dy * fwy[k]) * fs[k];
+        if (g.eta > 0.0) {
+          double k0, k1z;
+          k0_k1z_64(kap2 * (dx * dx + dy * dy), k0, k1z, g.tab);
+          const double wk = sqrt(fwx[k] * fwx[k] + fwy[k] * fwy[k]);   // the normal is a unit vector
+          sum += (k1z * (dx * fwx[k] + dy * fwy[k]) + ek * k0 * wk) * fs[k];
+        } else {
+          sum += k1z_64(kap2 * (dx * dx + dy * dy), g.tab) * (dx * fwx[k] + dy * fwy[k]) * fs[k];
+        }
       }
       for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 64);
       if (lane == t) acc += sum;

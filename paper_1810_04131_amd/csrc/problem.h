@@ -148,6 +148,7 @@ struct yq_problem {
     g.fpan = fpan.p;
     g.zcut = zcut64;
     g.zcut_g = zcut64g;
+    g.eta = prm.sl_coupling;
     return g;
   }
 };

@@ -14,6 +14,9 @@
 //   P_l = a_l cos(l Delta) - l b_l sin(l Delta),  Q_l = a_l sin(l Delta) + l b_l cos(l Delta),
 //   value    (w/2pi) [ I_0 a_0 + 2 sum_l I_l P_l ],
 //   gradient (w/2pi) [ a_0 kappa I_0' rhat_x + 2 sum_l (P_l kappa I_l' rhat_x + Q_l (l/r) I_l thhat_x) ].
+// The single layer (eq. single-layer-def) has the coefficients (1/2pi) int K_l(kappa
+// r_y) e^{i l th_y} sigma ds, so the combined representation D + eta S (eq. bwform)
+// adds eta K_l(kappa r_y) to a_l.
 // sigma on the sub-panels is the Lagrange interpolant of the 16 coarse values.
 // The operator row is the mean of the exterior (+) and interior (-) expansions
 // plus 1/2 at the self node (1/2 sigma + p.v. D sigma, eq. djump / eq. bie);
@@ -28,7 +31,8 @@
 namespace yq {
 
 // Plain far-field coefficient and gradient of source j at target i (same
-// formulas as the far-field kernels, scaled by kappa^2 / 2pi).
+// formulas as the far-field kernels, scaled by kappa^2 / 2pi; with g.eta > 0 the
+// single layer's eta w G and eta w grad G are included).
 __device__ __forceinline__ void smooth_pair(const GeomView& g, double xi, double yi, int64_t j,
                                             double& s, double& sgx, double& sgy) {
   double dx = xi - g.x[j], dy = yi - g.y[j];
@@ -39,8 +43,9 @@ __device__ __forceinline__ void smooth_pair(const GeomView& g, double xi, double
   double c = kap2 / (2.0 * PI);
   double qx = g.wnx[j], qy = g.wny[j];
   double dq = dx * qx + dy * qy;
-  s = c * k1z * dq;
-  double b = dq * (k0 + 2.0 * k1z) * rcp64(r2);
+  const double ew = g.eta * g.w[j];
+  s = c * (k1z * dq + ew * k0 / kap2);
+  double b = dq * (k0 + 2.0 * k1z) * rcp64(r2) + ew * k1z;
   sgx = c * (k1z * qx - b * dx);
   sgy = c * (k1z * qy - b * dy);
 }
@@ -105,6 +110,8 @@ __global__ __launch_bounds__(BS) void qbx_build_kernel(GeomView g, int p, int wi
       const int64_t fo = fbase + sub * Q + gq;
       const double yfx = fx[fo], yfy = fy[fo];
       const double nfx = fwx[fo], nfy = fwy[fo];   // weight x normal
+      // eta x weight (the normal is a unit vector) for the single layer's coefficients
+      const double ew = g.eta > 0.0 ? g.eta * sqrt(nfx * nfx + nfy * nfy) : 0.0;
 
       double cval = 0.0, gr = 0.0, gt = 0.0;
 #pragma unroll
@@ -125,14 +132,14 @@ __global__ __launch_bounds__(BS) void qbx_build_kernel(GeomView g, int p, int wi
         double K0, K1;
         k01_64(z, K0, K1, g.tab);
         const double iz2 = 2.0 * rcp64(z);
-        const double a0 = -kap * K1 * rn;
+        const double a0 = -kap * K1 * rn + ew * K0;
         double sum = sI[0][tid] * a0;
         double g_r = a0 * kap * sI[1][tid];
         double g_t = 0.0;
         double Km = K0, Kc = K1, cl = cosD, sl = sinD;
         for (int l = 1; l <= p; ++l) {
           const double Kp = fma(l * iz2, Kc, Km);
-          const double a = -0.5 * kap * (Km + Kp) * rn;
+          const double a = -0.5 * kap * (Km + Kp) * rn + ew * Kc;
           const double b = Kc * tn * irf;
           const double Pl = a * cl - l * b * sl;
           const double Il = sI[l][tid];
@@ -197,7 +204,8 @@ __global__ __launch_bounds__(BS) void qbx_build_kernel(GeomView g, int p, int wi
 }
 
 // Oversampled direct rows for the extra near panels of each target
-// (nsub sub-panels, interpolated sigma), minus the plain far-field terms.
+// (nsub sub-panels, interpolated sigma), minus the plain far-field terms (both
+// layers of the combined representation when g.eta > 0).
 // vals[e*16 + m]; gvals[(e*2 + c)*16 + m].
 __global__ void near_rows_kernel(GeomView g, Consts c, int nsub, const double* __restrict__ L,
                                  const int* __restrict__ row_ptr, const int* __restrict__ panels,
@@ -233,8 +241,9 @@ __global__ void near_rows_kernel(GeomView g, Consts c, int nsub, const double* _
         double k0, k1z;
         k0_k1z_64(kap2 * r2, k0, k1z, g.tab);
         const double dq = dx * qx + dy * qy;
-        const double v = cst * k1z * dq;
-        const double b = dq * (k0 + 2.0 * k1z) * rcp64(r2);
+        const double ew = g.eta * wf;   // single layer of the combined representation
+        const double v = cst * (k1z * dq + ew * k0 / kap2);
+        const double b = dq * (k0 + 2.0 * k1z) * rcp64(r2) + ew * k1z;
         const double vx = cst * (k1z * qx - b * dx);
         const double vy = cst * (k1z * qy - b * dy);
         const double* Lr = L + (sub * Q + gq) * Q;

@@ -37,8 +37,8 @@
 #include <memory>
 #include <mutex>
 #include <string>
-#include <thread>
 
+#include "arena.h"
 #include "batch.h"
 #include "common.h"
 #include "problem.h"
@@ -127,8 +127,8 @@ struct yq_server {
   Engine eng;
   int64_t capacity = 0;
   int max_slots = 0;
-  double budget_bytes = 0.0, used_bytes = 0.0;
-  std::vector<std::pair<int64_t, int64_t>> free_ranges;  // (offset, length), sorted
+  MemBudget budget;     // device bytes of admitted requests (estimates)
+  NodeArena arena;      // node ranges of the fused lane's requests
   std::vector<Request*> slots;
   std::deque<Request*> queue;
   std::map<int64_t, std::unique_ptr<Request>> reqs;
@@ -148,7 +148,7 @@ struct yq_server {
   std::deque<Request*> fmm_queue;       // waiting for a worker (guarded by mu)
   std::vector<Request*> fmm_done;       // finished by a worker (guarded by mu)
   bool stop = false;                    // guarded by mu
-  std::vector<std::thread> workers;
+  std::vector<std::unique_ptr<HostThread>> workers;
 };
 
 namespace {
@@ -281,36 +281,8 @@ void stop_workers(yq_server* s) {
     s->stop = true;
   }
   s->cv.notify_all();
-  for (auto& t : s->workers) t.join();
+  for (auto& t : s->workers) t->join();
   s->workers.clear();
-}
-
-bool take_range(yq_server* s, int64_t N, int64_t& off) {
-  for (size_t k = 0; k < s->free_ranges.size(); ++k) {
-    auto& fr = s->free_ranges[k];
-    if (fr.second >= N) {
-      off = fr.first;
-      fr.first += N;
-      fr.second -= N;
-      if (fr.second == 0) s->free_ranges.erase(s->free_ranges.begin() + k);
-      return true;
-    }
-  }
-  return false;
-}
-
-void give_range(yq_server* s, int64_t off, int64_t N) {
-  auto& fr = s->free_ranges;
-  fr.push_back({off, N});
-  std::sort(fr.begin(), fr.end());
-  std::vector<std::pair<int64_t, int64_t>> merged;
-  for (auto& r : fr) {
-    if (!merged.empty() && merged.back().first + merged.back().second == r.first)
-      merged.back().second += r.second;
-    else
-      merged.push_back(r);
-  }
-  fr.swap(merged);
 }
 
 void sync_members(yq_server* s) {
@@ -355,12 +327,14 @@ int yq_server_create(const yq_params* params, int64_t node_capacity, int32_t max
     yq_destroy(probe);
     YQ_REQUIRE(params->far_mode != YQ_FAR_CUTOFF, YQ_EINVAL,
                "the cutoff far field is available to single problems only");
+    YQ_REQUIRE(params->sl_coupling == 0.0, YQ_EINVAL,
+               "the combined representation (sl_coupling > 0) is available to single problems only");
     auto s = std::make_unique<yq_server>();
     s->prm = *params;
     s->capacity = node_capacity;
     s->max_slots = max_slots;
-    s->budget_bytes = mem_budget_bytes;
-    s->free_ranges.push_back({0, node_capacity});
+    s->budget.limit = mem_budget_bytes;
+    s->arena.reset(node_capacity);
     s->slots.assign(max_slots, nullptr);
     s->eng.init(*params);
     s->eng.T = node_capacity;
@@ -426,7 +400,7 @@ int yq_server_submit(yq_server* s, int32_t n, const double* center_xy, const dou
     *ticket = r->id;
     Request* rp = r.get();
     s->reqs[r->id] = std::move(r);
-    if ((!rp->fmm_lane && rp->N > s->capacity) || rp->est_bytes > s->budget_bytes) {
+    if ((!rp->fmm_lane && rp->N > s->capacity) || rp->est_bytes > s->budget.limit) {
       fail_request(s, rp, YQ_EADMIT, "request exceeds the node capacity or the memory budget");
       throw Error{YQ_EADMIT, "request " + std::to_string(rp->id) +
                                  " exceeds the node capacity or the memory budget"};
@@ -447,7 +421,7 @@ int yq_server_step(yq_server* s, int32_t* completed, int32_t* running, int32_t* 
     for (auto it = s->queue.begin(); it != s->queue.end();) {
       Request* r = *it;
       if (r->fmm_lane) {
-        if (s->fmm_inflight >= s->fmm_workers || s->used_bytes + r->est_bytes > s->budget_bytes) {
+        if (s->fmm_inflight >= s->fmm_workers || !s->budget.fits(r->est_bytes)) {
           ++it;
           continue;
         }
@@ -456,10 +430,11 @@ int yq_server_step(yq_server* s, int32_t* completed, int32_t* running, int32_t* 
           // graph capture on the engine's stream must not overlap such calls,
           // so from here on the fused iteration is launched eagerly.
           s->eng.use_graphs = false;
-          while ((int)s->workers.size() < s->fmm_workers) s->workers.emplace_back(fmm_worker, s);
+          while ((int)s->workers.size() < s->fmm_workers)
+            s->workers.push_back(std::make_unique<HostThread>([s] { fmm_worker(s); }));
         }
         r->phase = RUNNING;
-        s->used_bytes += r->est_bytes;
+        s->budget.take(r->est_bytes);
         ++s->fmm_inflight;
         {
           std::lock_guard<std::mutex> lk(s->mu);
@@ -480,7 +455,7 @@ int yq_server_step(yq_server* s, int32_t* completed, int32_t* running, int32_t* 
         ++it;
         continue;
       }
-      if (s->used_bytes + r->est_bytes > s->budget_bytes || !take_range(s, r->N, off)) {
+      if (!s->budget.fits(r->est_bytes) || !s->arena.take(r->N, off)) {
         ++it;
         continue;
       }
@@ -497,7 +472,7 @@ int yq_server_step(yq_server* s, int32_t* completed, int32_t* running, int32_t* 
       if (st != YQ_OK) {
         fail_request(s, r, st, pb ? yq_last_error(pb) : "create failed");
         r->pb.reset();
-        give_range(s, off, r->N);
+        s->arena.give(off, r->N);
         it = s->queue.erase(it);
         continue;
       }
@@ -507,7 +482,7 @@ int yq_server_step(yq_server* s, int32_t* completed, int32_t* running, int32_t* 
       r->step = RESID;
       r->x_zero = true;
       s->slots[slot] = r;
-      s->used_bytes += r->est_bytes;
+      s->budget.take(r->est_bytes);
       it = s->queue.erase(it);
       changed = true;
     }
@@ -658,8 +633,8 @@ int yq_server_step(yq_server* s, int32_t* completed, int32_t* running, int32_t* 
       r->status = st == YQ_OK ? (r->rel <= s->prm.tol ? YQ_OK : YQ_ENOCONV) : st;
       if (st != YQ_OK) r->err = yq_last_error(r->pb.get());
       s->slots[c] = nullptr;
-      give_range(s, r->off, r->N);
-      s->used_bytes -= r->est_bytes;
+      s->arena.give(r->off, r->N);
+      s->budget.give(r->est_bytes);
       r->pb.reset();
       ++done_now;
       released = true;
@@ -673,7 +648,7 @@ int yq_server_step(yq_server* s, int32_t* completed, int32_t* running, int32_t* 
     }
     for (Request* r : fin) {
       --s->fmm_inflight;
-      s->used_bytes -= r->est_bytes;
+      s->budget.give(r->est_bytes);
       r->info.seconds = r->t_done - r->t_submit;
       if (r->cancel.load()) {
         r->status = YQ_ESTATE;
@@ -749,8 +724,8 @@ int yq_server_cancel(yq_server* s, int64_t ticket) {
       s->eng.upload_mask(s->eng.inc, one);
       s->eng.clear_active(s->eng.inc.p);
       s->slots[r->slot] = nullptr;
-      give_range(s, r->off, r->N);
-      s->used_bytes -= r->est_bytes;
+      s->arena.give(r->off, r->N);
+      s->budget.give(r->est_bytes);
       r->pb.reset();
       sync_members(s);
     } else {

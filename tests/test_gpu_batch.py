@@ -206,3 +206,98 @@ def test_batch_fmm_lane_matches_oracle_single_and_direct_batch(oracles):
     for c in range(2):
         s = slice(int(allf.offsets[c]), int(allf.offsets[c + 1]))
         assert ia[c]["residual"] <= 1e-10 and _rel(_np(sa)[s], oracles[c]["sigma"]) < 1e-8
+
+
+def _lane_batch(cfgs, graphs, **prm):
+    b = yq.Batch(yq.default_params(**prm))
+    b.set_fmm(5 * P * 16, workers=2)        # the 5-particle configuration takes the FMM lane
+    b.set_configs(cfgs)
+    b.use_graphs(graphs)
+    return b
+
+
+def test_batch_graph_replay_equals_eager_with_the_fmm_lane_active():
+    # the fused iteration stays graph-captured while lane workers solve beside it
+    _torch()
+    cfgs = _configs()
+    prm = dict(panels_per_particle=P, qbx_order=ORDER, tol=1e-10, precision=1)
+    e = _lane_batch(cfgs, False, **prm)
+    e.set_boundary_data(e.boundary_label())
+    se, ie = e.solve()
+    se = _np(se)
+    g = _lane_batch(cfgs, True, **prm)
+    g.set_boundary_data(g.boundary_label())
+    for rep in range(3):
+        sg, ig = g.solve()
+        assert np.array_equal(_np(sg), se), rep
+        assert [i["iterations"] for i in ig] == [i["iterations"] for i in ie]
+
+
+def test_batch_raw_abi_without_device_sync_between_calls():
+    # The batch calls are synchronous by contract: driven through the C ABI alone,
+    # with no device-wide synchronisation between set-up, boundary data and solve,
+    # the results equal those of the binding (which synchronises before each call).
+    import ctypes
+    torch = _torch()
+    cfgs = _configs()
+    prm = dict(panels_per_particle=P, qbx_order=ORDER, tol=1e-10, precision=1)
+    ref = _lane_batch(cfgs, True, **prm)
+    ref.set_boundary_data(ref.boundary_label())
+    sref, _ = ref.solve()
+    sref = _np(sref)
+
+    lib = yq._lib.load()
+    params = yq.default_params(**prm)
+    h = ctypes.c_void_p()
+    assert lib.yq_batch_create(ctypes.byref(params), ctypes.byref(h)) == 0
+    try:
+        assert lib.yq_batch_set_fmm(h, 5 * P * 16, 2) == 0
+        npart = np.ascontiguousarray([c.center.shape[0] for c in cfgs], dtype=np.int32)
+        cat = lambda k: np.ascontiguousarray(np.concatenate(
+            [np.asarray(getattr(c, k), float).reshape(-1) for c in cfgs]))
+        cen, ang, ax = cat("center"), cat("angle"), cat("axes")
+        kap = np.ascontiguousarray([float(c.kappa) for c in cfgs])
+        vp = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+        assert lib.yq_batch_set_configs(h, len(cfgs), vp(npart), vp(cen), vp(ang), vp(ax),
+                                        vp(kap)) == 0
+        total = ctypes.c_int64()
+        assert lib.yq_batch_num_nodes(h, ctypes.byref(total), None) == 0
+        f = torch.empty(total.value, dtype=torch.float64, device="cuda")
+        sig = torch.empty_like(f)
+        torch.cuda.synchronize()            # the buffers exist before the library writes them
+        assert lib.yq_batch_boundary_label(h, 0, ctypes.c_double(np.pi / 4),
+                                           ctypes.c_double(0.1), ctypes.c_void_p(f.data_ptr())) == 0
+        assert lib.yq_batch_set_boundary_data(h, ctypes.c_void_p(f.data_ptr())) == 0
+        infos = (yq.yq_solve_info * len(cfgs))()
+        assert lib.yq_batch_solve(h, ctypes.c_void_p(sig.data_ptr()), infos) == 0
+        assert np.array_equal(_np(sig), sref)
+    finally:
+        lib.yq_batch_destroy(h)
+
+
+def test_batch_far_field_timers_count_pairs_and_leave_results_unchanged():
+    torch = _torch()
+    cfgs = _configs()
+    prm = dict(tol=1e-10, precision=1)
+    ref = _batch(cfgs, **prm)
+    ref.set_boundary_data(ref.boundary_label())
+    s_ref, i_ref = ref.solve()
+    b = _batch(cfgs, **prm)
+    b.profile(True)
+    x = np.random.default_rng(3).standard_normal(b.total)
+    b.apply_operator(x, yq.YQ_MIXED)
+    n, ms, pairs = b.profile_read(yq.YQ_MIXED)
+    N = np.diff(b.offsets)
+    assert n == 1 and ms > 0.0 and pairs == float((N * N).sum())
+    b.apply_operator(x, yq.YQ_FP64)
+    n64, ms64, pairs64 = b.profile_read(yq.YQ_FP64)
+    assert n64 == 1 and ms64 > 0.0 and pairs64 == float((N * N).sum())
+    b.set_boundary_data(b.boundary_label())
+    s, infos = b.solve()                 # split graphs with events between them
+    assert np.array_equal(_np(s), _np(s_ref))
+    n, ms, pairs = b.profile_read(yq.YQ_MIXED)
+    fp32_matvecs = sum(i["matvecs_fp32"] for i in infos)
+    assert n >= max(i["matvecs_fp32"] for i in infos) and ms > 0.0
+    # every evaluated pair belongs to a configuration's own N^2 block
+    assert 0 < pairs <= float((N * N * np.array([i["matvecs_fp32"] + 2 for i in infos])).sum())
+    assert fp32_matvecs > 0

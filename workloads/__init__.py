@@ -31,6 +31,9 @@ __all__ = [
     "config_medium",
     "config_large",
     "batched_configs",
+    "batched_plan",
+    "batched_layout",
+    "batch_member_200",
     "serving_trace",
     "single_disk",
     "grid_ellipses",
@@ -215,21 +218,40 @@ def config_dynamics(seed: int = 0) -> dict:
                 gamma=1.0, c0=0.02, q=3, name="100 ellipses on a 10x10 grid, N=51200")
 
 
+def batched_plan(count: int, seed: int = 0, nmin: int = 10, nmax: int = 200,
+                 kappa_range=(0.5, 2.0)) -> List[dict]:
+    """The draws of `batched_configs` (particle count, kappa, layout seed per
+    configuration) without the layouts, which `batched_layout` makes one by one."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for c in range(count):
+        n = int(round(math.exp(rng.uniform(math.log(nmin), math.log(nmax)))))
+        kappa = float(rng.uniform(*kappa_range))
+        out.append(dict(id=c, n=n, kappa=kappa, seed=int(rng.integers(2**31))))
+    return out
+
+
+def batched_layout(item: dict) -> Particles:
+    n = item["n"]
+    return random_ellipses(n, 30.0 * math.sqrt(n / 50.0), item["kappa"], seed=item["seed"],
+                           gap=0.2, name=f"batch {item['id']}: {n} ellipses")
+
+
 def batched_configs(count: int, seed: int = 0, nmin: int = 10, nmax: int = 200,
                     kappa_range=(0.5, 2.0)) -> List[Particles]:
     """`count` independent configurations with log-uniform particle counts in [nmin, nmax].
 
     Box side L = 30 sqrt(n/50) keeps the 50-in-30x30 density; kappa ~ U(kappa_range).
     """
-    rng = np.random.default_rng(seed)
-    out = []
-    for c in range(count):
-        n = int(round(math.exp(rng.uniform(math.log(nmin), math.log(nmax)))))
-        kappa = float(rng.uniform(*kappa_range))
-        box = 30.0 * math.sqrt(n / 50.0)
-        out.append(random_ellipses(n, box, kappa, seed=int(rng.integers(2**31)), gap=0.2,
-                                   name=f"batch {c}: {n} ellipses"))
-    return out
+    return [batched_layout(it) for it in batched_plan(count, seed, nmin, nmax, kappa_range)]
+
+
+def batch_member_200() -> Particles:
+    """A 200-ellipse configuration drawn like the batched workload's largest members
+    (box 30 sqrt(200/50) = 60, gap 0.2, axes 1.0 x 0.5, kappa 1.7, seed 11)."""
+    n = 200
+    return random_ellipses(n, 30.0 * math.sqrt(n / 50.0), 1.7, seed=11, gap=0.2,
+                           name="200-ellipse batch member")
 
 
 def serving_trace(count: int, rate: float = 200.0, seed: int = 0, nmin: int = 10,
