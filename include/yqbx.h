@@ -231,6 +231,21 @@ int yq_solve_forces(yq_problem* prob, const double* sigma0, double* sigma, yq_so
 int yq_eval_potential(yq_problem* prob, const double* sigma, int64_t M, const double* tx,
                       const double* ty, double* u);
 
+/* yq_eval_potential without device allocation, for callers that cannot allocate
+ * device memory (code under HIP stream capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments and results as yq_eval_potential (the
+ * same kernels).  Its scratch (the chunk partial sums and the oversampled panel
+ * rule) lives in one device array of 64 MiB that the library holds on every
+ * device it runs on until the process ends; the call allocates nothing and
+ * rebuilds the oversampled points each time.  YQ_EINVAL when a call would need
+ * more than 64 MiB: about 8 (chunks x M + 5 x panels x pot_oversample x 16)
+ * bytes, e.g. 10 MB for 1,024 targets on 1,600 panels at oversampling 8.  All
+ * calls on one device share the array: calls that overlap in time on one device
+ * (two streams, two threads) race and must be serialised by the caller; calls
+ * queued on one stream are ordered.  Asynchronous on the problem's stream. */
+int yq_eval_potential_noalloc(yq_problem* prob, const double* sigma, int64_t M, const double* tx,
+                              const double* ty, double* u);
+
 /* ---- Time stepping ---------------------------------------------------------------------
  * Excluded-volume repulsion (eq. repul) with the three-circle model of ellipses
  * (supplementary section S1): particle i is three circles of radius B_i centred

@@ -109,6 +109,7 @@ SIGNATURES = {
     "yq_solve_forces": (c_int32, [P, P, P, ctypes.POINTER(yq_solve_info), c_double, P, P,
                                   ctypes.POINTER(c_double)]),
     "yq_eval_potential": (c_int32, [P, P, c_int64, P, P, P]),
+    "yq_eval_potential_noalloc": (c_int32, [P, P, c_int64, P, P, P]),
     "yq_repulsion": (c_int32, [P, c_double, c_int32, P, P, ctypes.POINTER(c_double)]),
     "yq_step": (c_int32, [P, ctypes.POINTER(yq_dynamics), P, P, ctypes.POINTER(yq_solve_info), P,
                           P, P]),
