@@ -140,9 +140,12 @@ def parse():
                     help="batch/serve: largest particle count (default 200 batch, 2000 serve)")
     ap.add_argument("--fmm-workers", type=int, default=3,
                     help="serve/batch: FMM-lane worker threads")
-    ap.add_argument("--batch-lane", choices=["hybrid", "fused"], default="hybrid",
+    ap.add_argument("--batch-lane", choices=["hybrid", "fused", "engine"], default="hybrid",
                     help="batch: hybrid = configurations from --fmm-min-nodes on take the FMM "
-                         "lane; fused = every configuration in the fused direct engine")
+                         "lane; fused = every configuration in the fused direct engine; engine "
+                         "= only the configurations below --fmm-min-nodes (the fused engine's "
+                         "members of the hybrid run, without the lane's worker threads: the "
+                         "command for counter runs of the fused kernels)")
     ap.add_argument("--fmm-min-nodes", type=int, default=20000,
                     help="serve: requests of at least this many nodes take the FMM lane")
     ap.add_argument("--fp64-requests", type=int, default=None,
@@ -179,6 +182,37 @@ def counters(key):
         return float(kv[key])
     except (KeyError, ValueError):
         return None
+
+
+BATCH_COUNTERS_FILE = "profiles/bfar32_kernel_batch_engine_counters.txt"
+BATCH_SRC = ["paper_1810_04131_amd/csrc/batch.hip", "paper_1810_04131_amd/csrc/farfield_core.h",
+             "paper_1810_04131_amd/csrc/bessel.h", "paper_1810_04131_amd/csrc/bessel_tables.h"]
+
+
+def batch_counters():
+    """Per-pair HBM bytes and VALU figures of bfar32_kernel from the committed counter
+    summary, or {} when the kernel's source has changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, BATCH_COUNTERS_FILE)
+    if not os.path.exists(path):
+        return {}
+    h = hashlib.sha256()
+    for f in BATCH_SRC:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    kv = {}
+    for line in open(path):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.strip().split("=", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("source_sha256_16") != h.hexdigest()[:16]:
+        return {}
+    out = {}
+    for k, v in kv.items():
+        try:
+            out[k] = float(v)
+        except ValueError:
+            pass
+    return out
 
 
 def traffic_from_counters(launch_pairs):
@@ -359,6 +393,9 @@ def bench_batch(args):
     t0 = time.perf_counter()
     cfgs = batch_layouts(plan)
     log(f"{len(cfgs)} configurations drawn in {time.perf_counter() - t0:.1f} s")
+    engine_only = args.batch_lane == "engine"
+    if engine_only:
+        cfgs = [c for c in cfgs if c.n * 512 < args.fmm_min_nodes]
     hybrid = args.batch_lane == "hybrid"
     thr = args.fmm_min_nodes if hybrid else None
     tol = args.tol
@@ -457,6 +494,7 @@ def bench_batch(args):
     # source-target pair (the design's count for the FP32 kernel evaluation);
     # pairs = what the timed launches evaluated (configurations still iterating)
     F32_ALG, F64_ALG = 40.0, 50.0
+    bc = batch_counters()
     avg32 = ms32 / max(n32, 1)
     achieved = F32_ALG * pairs32 / (ms32 * 1e-3) if ms32 > 0 else 0.0
     out = {
@@ -475,7 +513,9 @@ def bench_batch(args):
                                   f"{int(lane.sum())} from {thr} nodes on in the FMM lane "
                                   f"({args.fmm_workers} workers, FMM order 20 inner / 40 FP64 "
                                   f"residuals)" if hybrid
-                                  else "every configuration in the fused direct engine"),
+                                  else ("the configurations below %d nodes only, all in the fused "
+                                        "direct engine" % args.fmm_min_nodes if engine_only
+                                        else "every configuration in the fused direct engine")),
                    "configs": len(cfgs), "total_nodes": int(N.sum()),
                    "parallelism": "single GPU"},
         "solves_per_s": len(cfgs) / t_step,
@@ -494,7 +534,12 @@ def bench_batch(args):
         "errors_vs_oracle": errors_vs_oracle_c2(yq, tol),
         "roofline": {"bound": "alu", "kernel": "bfar32_kernel", "achieved": achieved / 1e12,
                      "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32,
-                     "traffic": None, "flops_per_pair": F32_ALG,
+                     "traffic": (bc["hbm_bytes_per_pair"] * pairs32 / max(n32, 1)
+                                 if "hbm_bytes_per_pair" in bc else None),
+                     "flops_per_pair": F32_ALG,
+                     "counter_flops_per_pair": bc.get("valu_flops_per_pair"),
+                     "counter_frac": (bc["valu_flops_per_pair"] * pairs32 / (ms32 * 1e-3) / PEAK_FP32
+                                      if "valu_flops_per_pair" in bc and ms32 > 0 else None),
                      "pairs_per_launch": pairs32 / max(n32, 1), "avg_launch_ms": avg32,
                      "launches": n32,
                      "fp64_kernel": {"kernel": "bfar64_kernel", "launches": n64,

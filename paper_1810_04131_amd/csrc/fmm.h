@@ -21,6 +21,8 @@ struct FmmLevel {
   double2* L = nullptr;
 };
 
+struct M2LLevels;   // per-level views of the M2L kernels (fmm.hip)
+
 struct Fmm {
   int p = 20;
   int depth = 0;
@@ -56,6 +58,8 @@ struct Fmm {
   bool want_m2l32 = false;
   DevBuf<float> amat32;   // scaled M2L matrices, the operand order of amat
   DevBuf<double> msc;     // s_n per level [level][n]
+  DevBuf<double> mpk64;   // multipoles packed as M2L operands, FP64 [box][R16]
+  DevBuf<float> mpk32;    // the same scaled by s_n, FP32
   PinnedBuf stage_up, stage_dn;   // set-up transfers (grow-only, reused by every build)
   DevBuf<char> stage_dev;         // device side of the batched uploads and copies
   DevBuf<double> bbox;            // node bounding box (xmin, xmax, ymin, ymax)
@@ -80,6 +84,9 @@ struct Fmm {
   void copy_tree(const Fmm& o, int q, const double* tab, hipStream_t s);
   // partial[i] = (2 pi / kappa^2) * far field at node i (the far-field kernels' scaling)
   // stop (optional device flag): the heavy kernels do nothing once it is set
+  M2LLevels m2l_levels() const;
+  template <typename T>
+  void m2l_run(hipStream_t s, const int* stop, DevBuf<T>& mp, const T* A);
   void m2l_mfma(hipStream_t s, const int* stop = nullptr);
   void m2l_mfma32(hipStream_t s, const int* stop = nullptr);
   void tree_mfma(bool gather, int l, hipStream_t s);

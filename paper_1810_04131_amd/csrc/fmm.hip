@@ -322,21 +322,33 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 constexpr int DMAX = 14;   // deepest quadtree level
 
-// Translation matrices in the operand order of the 16x16x4 product: for
-// (level, slot, row tile rt, k step ks) the 64 values lane by lane, lane =
-// i + 16 kk holding A[16 rt + i][4 ks + kk], so that a wave's operand load is
-// one coalesced row.  A slot is an M2L offset (49 per level, table ts, sign
-// (-1)^m) or a child position (4 per level, table tg, no sign; M2M and L2L
-// use the same matrices).
-__global__ void trans_amat_kernel(int nlev, int nslot, int p, int R, int alt_sign,
+// Translation matrices in the operand order of the 16x16x4 product: lane =
+// i + 16 kk holds A[16 rt + i][4 ks + kk].  Row order (packed = 0, the M2M and
+// L2L matrices): for (level, slot, row tile rt, k step ks) the 64 values lane by
+// lane, so that a wave's operand load is one coalesced row.  Lane order (packed =
+// 1, the M2L matrices): for (level, slot, rt) the KS = R / 4 values of each lane
+// in a row, [(rt * 64 + lane) * KS + ks], so that a lane loads its KS operands
+// with a few wide loads.  A slot is an M2L offset (49 per level, table ts, sign
+// (-1)^m) or a child position (4 per level, table tg, no sign).
+__global__ void trans_amat_kernel(int nlev, int nslot, int p, int R, int alt_sign, int packed,
                                   const double2* __restrict__ tab, double* __restrict__ amat) {
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int64_t per = (int64_t)R * R;        // values per (level, slot)
   if (t >= (int64_t)nlev * nslot * per) return;
   const int64_t lo = t / per;                // level * nslot + slot
   const int rem = (int)(t % per);
-  const int lane = rem & 63, tile = rem >> 6;          // tile = rt * (R / 4) + ks
-  const int rt = tile / (R / 4), ks = tile % (R / 4);
+  int lane, rt, ks;
+  if (packed) {
+    const int KS = R / 4, q = rem / KS;
+    ks = rem % KS;
+    lane = q & 63;
+    rt = q >> 6;
+  } else {
+    const int tile = rem >> 6;                           // tile = rt * (R / 4) + ks
+    lane = rem & 63;
+    rt = tile / (R / 4);
+    ks = tile % (R / 4);
+  }
   const int r = 16 * rt + (lane & 15), k = 4 * ks + (lane >> 4);
   const int P1 = p + 1;
   double v = 0.0;
@@ -425,50 +437,11 @@ struct M2LLevels {
   const double2* M[DMAX + 1];
   double2* L[DMAX + 1];
   int nbox[DMAX + 1];
+  int64_t off[DMAX + 2];     // first box of each level in the packed multipoles (off[depth + 1] = total)
 };
 
-// One block (4 waves) per (16-box tile, row tile); wave w takes far offsets
-// w, w + 4, ..., loading the next offset's operands while the current one's
-// products run.
-template <int RT>
-__global__ __launch_bounds__(256) void m2l_mfma_kernel(int p, const int2* __restrict__ tiles,
-                                                       M2LLevels lv, const double* __restrict__ amat,
-                                                       int64_t level_stride,
-                                                       const int* __restrict__ stop) {
-  if (stop && *stop) return;
-  constexpr int R = RT * 16, KS = R / 4, NI = 10;
-  __shared__ dbl4 red[3 * 64];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int2 tl = tiles[blockIdx.x / RT];       // (level, first box)
-  const int rt = blockIdx.x % RT;
-  const int l = tl.x, nbox = lv.nbox[l];
-  const int* __restrict__ ild = lv.ild[l];
-  const double2* __restrict__ M = lv.M[l];
-  const int P1 = p + 1;
-  const int col = lane & 15, kk = lane >> 4;
-  const int tb = tl.y + col;
-  const double* Al = amat + l * level_stride + (int64_t)rt * KS * 64 + lane;
-  int src[NI];
-#pragma unroll
-  for (int i = 0; i < NI; ++i) src[i] = tb < nbox ? ild[(int64_t)tb * 49 + far_offset(wave + 4 * i)] : -1;
-  auto A_of = [&](int i) { return Al + (int64_t)far_offset(wave + 4 * i) * R * R; };
-  auto M_of = [&](int i) { return src[i] >= 0 ? M + (int64_t)src[i] * P1 : nullptr; };
-  TileOps<KS> o0, o1;
-  dbl4 acc = dbl4{0.0, 0.0, 0.0, 0.0};
-  tile_load<KS>(o0, A_of(0), M_of(0), P1, kk);
-#pragma unroll
-  for (int i = 0; i < NI; i += 2) {
-    tile_load<KS>(o1, A_of(i + 1), M_of(i + 1), P1, kk);
-    acc = tile_mfma<KS>(o0, acc);
-    if (i + 2 < NI) tile_load<KS>(o0, A_of(i + 2), M_of(i + 2), P1, kk);
-    acc = tile_mfma<KS>(o1, acc);
-  }
-  acc = block_tile_sum(acc, red);
-  if (wave == 0 && tb < nbox) tile_store<false>(lv.L[l] + (int64_t)tb * P1, rt, kk, P1, acc);
-}
-
-// Scaled FP32 copy of the M2L matrices (operand order as in trans_amat_kernel):
-// amat32 = A_mn / (s_m s_n), s = msc of the matrix's level.
+// Scaled FP32 copy of the M2L matrices (the lane order of trans_amat_kernel with
+// packed = 1): amat32 = A_mn / (s_m s_n), s = msc of the matrix's level.
 __global__ void trans_amat32_kernel(int nlev, int p, int R, const double* __restrict__ amat,
                                     const double* __restrict__ msc, float* __restrict__ amat32) {
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -476,8 +449,8 @@ __global__ void trans_amat32_kernel(int nlev, int p, int R, const double* __rest
   if (t >= (int64_t)nlev * 49 * per) return;
   const int l = (int)(t / (49 * per));
   const int rem = (int)(t % per);
-  const int lane = rem & 63, tile = rem >> 6;
-  const int rt = tile / (R / 4), ks = tile % (R / 4);
+  const int KS = R / 4, q = rem / KS, ks = rem % KS;
+  const int lane = q & 63, rt = q >> 6;
   const int r = 16 * rt + (lane & 15), k = 4 * ks + (lane >> 4);
   const int P1 = p + 1;
   float v = 0.0f;
@@ -488,79 +461,109 @@ __global__ void trans_amat32_kernel(int nlev, int p, int R, const double* __rest
   amat32[t] = v;
 }
 
-// FP32 counterpart of m2l_mfma_kernel (inner applies only): B operands are the
-// scaled multipole coefficients M_n s_n rounded to FP32, products accumulate in
-// FP32 (v_mfma_f32_16x16x4f32), the four waves' tiles are summed in FP64 and
-// L_m = (sum) s_m is stored in FP64.  FP32 16x16 result layout: lane l holds
-// column l % 16, its register j row 4 (l / 16) + j.
-template <int RT>
-__global__ __launch_bounds__(256) void m2l_mfma32_kernel(int p, const int2* __restrict__ tiles,
-                                                         M2LLevels lv,
-                                                         const float* __restrict__ amat32,
-                                                         int64_t level_stride,
-                                                         const double* __restrict__ msc,
-                                                         const int* __restrict__ stop) {
+// Multipole coefficients of the boxes [g0, g1) (levels >= 2) as the B operands of
+// the M2L products: box g's row x = (Re M_0..Re M_p, Im M_0..Im M_p, zero padding
+// to R) stored lane by lane, Mp[g R + kk KS + ks] = x[4 ks + kk], so that the lane
+// with kk = lane / 16 loads its KS operands with a few wide loads.  T = float
+// scales by s_n of the box's level (msc) for the FP32 products.
+template <typename T>
+__global__ void m2l_pack_kernel(int p, int R, int64_t g0, int64_t g1, M2LLevels lv,
+                                const double2* __restrict__ Mall, const double* __restrict__ msc,
+                                T* __restrict__ Mp) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= (g1 - g0) * R) return;
+  const int64_t g = g0 + t / R;
+  const int e = (int)(t % R);
+  const int KS = R / 4, kk = e / KS, ks = e % KS;
+  const int k = 4 * ks + kk;
+  const int P1 = p + 1;
+  double v = 0.0;
+  if (k < 2 * P1) {
+    const int n = k < P1 ? k : k - P1;
+    const double2 m = Mall[g * P1 + n];
+    v = k < P1 ? m.x : m.y;
+    if (sizeof(T) == 4) {
+      int l = 2;
+      while (g >= lv.off[l + 1]) ++l;
+      v *= msc[(int64_t)l * P1 + n];
+    }
+  }
+  Mp[g * R + e] = (T)v;
+}
+
+// M2L on the matrix cores: L_m(t) = sum over the 40 far offsets o of A_o M(source at
+// o), for one 16-box tile of one level per block (4 waves; wave w takes offsets w,
+// w + 4, ...).  A wave loads each offset's 16 source vectors once (zero where a
+// target has no source there; offsets with no source in the tile are skipped) and
+// multiplies them with all RT row tiles of A_o.  T = double: FP64 products
+// (v_mfma_f64_16x16x4f64); T = float: FP32 products (v_mfma_f32_16x16x4f32) on the
+// scaled operands M_n s_n and A_mn / (s_m s_n), which keeps entries O(1) inside the
+// FP32 range, and L_m = (sum) s_m.  The four waves' tiles are summed in FP64 in a
+// fixed order.  Result layouts: FP64, lane l holds column l % 16, register j row
+// 4 j + l / 16; FP32, column l % 16, register j row 4 (l / 16) + j.
+template <typename T, int RT>
+__global__ __launch_bounds__(256) void m2l_mfma_kernel(int p, const int2* __restrict__ tiles,
+                                                       M2LLevels lv, const T* __restrict__ amat,
+                                                       const T* __restrict__ Mp,
+                                                       const double* __restrict__ msc,
+                                                       const int* __restrict__ stop) {
   if (stop && *stop) return;
   constexpr int R = RT * 16, KS = R / 4, NI = 10;
-  __shared__ dbl4 red[3 * 64];
+  constexpr bool F32 = sizeof(T) == 4;
+  using acc_t = typename std::conditional<F32, f32x4, dbl4>::type;
+  __shared__ dbl4 red[3 * RT * 64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int2 tl = tiles[blockIdx.x / RT];
-  const int rt = blockIdx.x % RT;
+  const int2 tl = tiles[blockIdx.x];       // (level, first box)
   const int l = tl.x, nbox = lv.nbox[l];
   const int* __restrict__ ild = lv.ild[l];
-  const double2* __restrict__ M = lv.M[l];
   const int P1 = p + 1;
-  const double* sc = msc + (int64_t)l * P1;
   const int col = lane & 15, kk = lane >> 4;
   const int tb = tl.y + col;
-  const float* Al = amat32 + l * level_stride + (int64_t)rt * KS * 64 + lane;
-  double bs[KS];   // scale of this lane's B rows
+  const T* Ml = Mp + lv.off[l] * R + kk * KS;
+  const T* Al = amat + (int64_t)l * 49 * RT * 64 * KS + (int64_t)lane * KS;
+  acc_t acc[RT];
 #pragma unroll
-  for (int ks = 0; ks < KS; ++ks) {
-    const int k = 4 * ks + kk;
-    bs[ks] = k < 2 * P1 ? sc[k < P1 ? k : k - P1] : 0.0;
-  }
-  int src[NI];
+  for (int rt = 0; rt < RT; ++rt) acc[rt] = acc_t{0, 0, 0, 0};
+  for (int i = 0; i < NI; ++i) {
+    const int o = far_offset(wave + 4 * i);
+    const int src = tb < nbox ? ild[(int64_t)tb * 49 + o] : -1;
+    if (__ballot(src >= 0) == 0) continue;    // no source at this offset in the tile
+    T b[KS];
+    const T* mb = Ml + (int64_t)(src >= 0 ? src : 0) * R;
 #pragma unroll
-  for (int i = 0; i < NI; ++i) src[i] = tb < nbox ? ild[(int64_t)tb * 49 + far_offset(wave + 4 * i)] : -1;
-  f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-  float a0[KS], b0[KS], a1[KS], b1[KS];
-  auto load = [&](int i, float* a, float* b) {
-    const float* A = Al + (int64_t)far_offset(wave + 4 * i) * R * R;
-    const double2* ms = src[i] >= 0 ? M + (int64_t)src[i] * P1 : nullptr;
+    for (int ks = 0; ks < KS; ++ks) b[ks] = src >= 0 ? mb[ks] : T(0);
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
-      a[ks] = A[ks * 64];
-      const int k = 4 * ks + kk;
-      double v = 0.0;
-      if (ms != nullptr && k < 2 * P1) {
-        const double2 mv = ms[k < P1 ? k : k - P1];
-        v = (k < P1 ? mv.x : mv.y) * bs[ks];
+    for (int rt = 0; rt < RT; ++rt) {
+      const T* A = Al + ((int64_t)o * RT + rt) * 64 * KS;
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        if constexpr (F32)
+          acc[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(A[ks], b[ks], acc[rt], 0, 0, 0);
+        else
+          acc[rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(A[ks], b[ks], acc[rt], 0, 0, 0);
       }
-      b[ks] = (float)v;
     }
-  };
-  load(0, a0, b0);
-#pragma unroll
-  for (int i = 0; i < NI; i += 2) {
-    load(i + 1, a1, b1);
-#pragma unroll
-    for (int ks = 0; ks < KS; ++ks) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[ks], b0[ks], acc, 0, 0, 0);
-    if (i + 2 < NI) load(i + 2, a0, b0);
-#pragma unroll
-    for (int ks = 0; ks < KS; ++ks) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[ks], b1[ks], acc, 0, 0, 0);
   }
-  dbl4 acd = {(double)acc[0], (double)acc[1], (double)acc[2], (double)acc[3]};
-  acd = block_tile_sum(acd, red);
-  if (wave == 0 && tb < nbox) {
-    double2* y = lv.L[l] + (int64_t)tb * P1;
+  if (wave > 0)
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+      red[((wave - 1) * RT + rt) * 64 + lane] =
+          dbl4{(double)acc[rt][0], (double)acc[rt][1], (double)acc[rt][2], (double)acc[rt][3]};
+  __syncthreads();
+  if (wave != 0 || tb >= nbox) return;
+  double2* y = lv.L[l] + (int64_t)tb * P1;
+  const double* sc = F32 ? msc + (int64_t)l * P1 : nullptr;
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt) {
+    dbl4 v = {(double)acc[rt][0], (double)acc[rt][1], (double)acc[rt][2], (double)acc[rt][3]};
+    for (int w = 0; w < 3; ++w) v += red[(w * RT + rt) * 64 + lane];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const int r = rt * 16 + 4 * kk + j;
+      const int r = F32 ? rt * 16 + 4 * kk + j : rt * 16 + 4 * j + kk;
       if (r < P1)
-        y[r].x = acd[j] * sc[r];
+        y[r].x = F32 ? v[j] * sc[r] : v[j];
       else if (r < 2 * P1)
-        y[r - P1].y = acd[j] * sc[r - P1];
+        y[r - P1].y = F32 ? v[j] * sc[r - P1] : v[j];
     }
   }
 }
@@ -1134,11 +1137,11 @@ void Fmm::set_order(int q, const double* tab, hipStream_t s) {
   if (use_mfma) {
     const int64_t vals = (int64_t)(depth + 1) * 49 * R16 * R16;
     amat.fit((size_t)vals);
-    trans_amat_kernel<<<(unsigned)((vals + 255) / 256), 256, 0, s>>>(depth + 1, 49, p, R16, 1, ts.p,
+    trans_amat_kernel<<<(unsigned)((vals + 255) / 256), 256, 0, s>>>(depth + 1, 49, p, R16, 1, 1, ts.p,
                                                                        amat.p);
     const int64_t gvals = (int64_t)(depth + 1) * 4 * R16 * R16;
     gmat.fit((size_t)gvals);
-    trans_amat_kernel<<<(unsigned)((gvals + 255) / 256), 256, 0, s>>>(depth + 1, 4, p, R16, 0, tg.p,
+    trans_amat_kernel<<<(unsigned)((gvals + 255) / 256), 256, 0, s>>>(depth + 1, 4, p, R16, 0, 0, tg.p,
                                                                         gmat.p);
     YQ_HIP(hipGetLastError());
     // 16-box tiles of every level with M2L terms, finest level first
@@ -1237,53 +1240,49 @@ void Fmm::copy_tree(const Fmm& o, int q, const double* tab, hipStream_t s) {
   set_order(q, tab, s);
 }
 
-void Fmm::m2l_mfma(hipStream_t s, const int* stop) {
+M2LLevels Fmm::m2l_levels() const {
   M2LLevels a{};
-  for (int l = 2; l <= depth; ++l) {
-    a.ild[l] = lv[l].ild.p;
+  for (int l = 0; l <= depth; ++l) {
+    a.ild[l] = l >= 2 ? lv[l].ild.p : nullptr;
     a.M[l] = lv[l].M;
     a.L[l] = lv[l].L;
     a.nbox[l] = lv[l].nbox;
+    a.off[l] = lv[l].off;
   }
-  const int RT = R16 / 16;
-  const unsigned g = (unsigned)(n_m2l_tiles * RT);   // one block per (tile, row tile)
-  if (g == 0) return;
-  const int64_t ls = (int64_t)49 * R16 * R16;
-  switch (RT) {
-    case 1: m2l_mfma_kernel<1><<<g, 256, 0, s>>>(p, m2l_tiles.p, a, amat.p, ls, stop); break;
-    case 2: m2l_mfma_kernel<2><<<g, 256, 0, s>>>(p, m2l_tiles.p, a, amat.p, ls, stop); break;
-    case 3: m2l_mfma_kernel<3><<<g, 256, 0, s>>>(p, m2l_tiles.p, a, amat.p, ls, stop); break;
-    case 4: m2l_mfma_kernel<4><<<g, 256, 0, s>>>(p, m2l_tiles.p, a, amat.p, ls, stop); break;
-    case 5: m2l_mfma_kernel<5><<<g, 256, 0, s>>>(p, m2l_tiles.p, a, amat.p, ls, stop); break;
-    case 6: m2l_mfma_kernel<6><<<g, 256, 0, s>>>(p, m2l_tiles.p, a, amat.p, ls, stop); break;
-    default: m2l_mfma_kernel<7><<<g, 256, 0, s>>>(p, m2l_tiles.p, a, amat.p, ls, stop); break;
+  a.off[depth + 1] = nbox_total;
+  return a;
+}
+
+// Packs the multipoles of levels >= 2 (m2l_pack_kernel) and runs the M2L of all
+// levels in one launch, one block per 16-box tile.
+template <typename T>
+void Fmm::m2l_run(hipStream_t s, const int* stop, DevBuf<T>& mp, const T* A) {
+  if (n_m2l_tiles == 0 || depth < 2) return;
+  const M2LLevels a = m2l_levels();
+  const int64_t g0 = lv[2].off, g1 = nbox_total;
+  mp.fit((size_t)nbox_total * R16);
+  const int64_t nt = (g1 - g0) * R16;
+  m2l_pack_kernel<T><<<(unsigned)((nt + 255) / 256), 256, 0, s>>>(p, R16, g0, g1, a, Mall.p, msc.p,
+                                                                   mp.p);
+  YQ_HIP(hipGetLastError());
+  const unsigned g = (unsigned)n_m2l_tiles;
+#define YQ_M2L(rt) m2l_mfma_kernel<T, rt><<<g, 256, 0, s>>>(p, m2l_tiles.p, a, A, mp.p, msc.p, stop)
+  switch (R16 / 16) {
+    case 1: YQ_M2L(1); break;
+    case 2: YQ_M2L(2); break;
+    case 3: YQ_M2L(3); break;
+    case 4: YQ_M2L(4); break;
+    case 5: YQ_M2L(5); break;
+    case 6: YQ_M2L(6); break;
+    default: YQ_M2L(7); break;
   }
+#undef YQ_M2L
   YQ_HIP(hipGetLastError());
 }
 
-void Fmm::m2l_mfma32(hipStream_t s, const int* stop) {
-  M2LLevels a{};
-  for (int l = 2; l <= depth; ++l) {
-    a.ild[l] = lv[l].ild.p;
-    a.M[l] = lv[l].M;
-    a.L[l] = lv[l].L;
-    a.nbox[l] = lv[l].nbox;
-  }
-  const int RT = R16 / 16;
-  const unsigned g = (unsigned)(n_m2l_tiles * RT);
-  if (g == 0) return;
-  const int64_t ls = (int64_t)49 * R16 * R16;
-  switch (RT) {
-    case 1: m2l_mfma32_kernel<1><<<g, 256, 0, s>>>(p, m2l_tiles.p, a, amat32.p, ls, msc.p, stop); break;
-    case 2: m2l_mfma32_kernel<2><<<g, 256, 0, s>>>(p, m2l_tiles.p, a, amat32.p, ls, msc.p, stop); break;
-    case 3: m2l_mfma32_kernel<3><<<g, 256, 0, s>>>(p, m2l_tiles.p, a, amat32.p, ls, msc.p, stop); break;
-    case 4: m2l_mfma32_kernel<4><<<g, 256, 0, s>>>(p, m2l_tiles.p, a, amat32.p, ls, msc.p, stop); break;
-    case 5: m2l_mfma32_kernel<5><<<g, 256, 0, s>>>(p, m2l_tiles.p, a, amat32.p, ls, msc.p, stop); break;
-    case 6: m2l_mfma32_kernel<6><<<g, 256, 0, s>>>(p, m2l_tiles.p, a, amat32.p, ls, msc.p, stop); break;
-    default: m2l_mfma32_kernel<7><<<g, 256, 0, s>>>(p, m2l_tiles.p, a, amat32.p, ls, msc.p, stop); break;
-  }
-  YQ_HIP(hipGetLastError());
-}
+void Fmm::m2l_mfma(hipStream_t s, const int* stop) { m2l_run<double>(s, stop, mpk64, amat.p); }
+
+void Fmm::m2l_mfma32(hipStream_t s, const int* stop) { m2l_run<float>(s, stop, mpk32, amat32.p); }
 
 // M2M into parent level l (gather) or L2L from parent level l (scatter), both
 // with the child level's position matrices.
