@@ -84,12 +84,13 @@ def _sub_interp(q, nsub):
 
 def qbx_panels(disc, i):
     """The panels whose contribution at target i goes through its expansion: the
-    target's own panel k and the qbx_window panels on either side of it."""
-    P = disc.params.panels
+    target's own panel and the qbx_window panels on either side of it along its
+    particle's ring of panels."""
     win = disc.params.qbx_window
     p = disc.particle[i]
-    k = disc.panel[i] - p * P
-    return [p * P + (k + o) % P for o in range(-win, win + 1)]
+    first, m = int(disc.poff[p]), int(disc.poff[p + 1] - disc.poff[p])
+    k = int(disc.panel[i]) - first
+    return [first + (k + o) % m for o in range(-win, win + 1)]
 
 
 def near_panels(disc, i):
@@ -131,9 +132,8 @@ def qbx_row(disc, i, side=1, gradient=False):
     vals = np.zeros((len(panels), q))
     grads = np.zeros((len(panels), q, 2))
     for j, J in enumerate(panels):
-        k = J - pid * P
-        y, ny, wy, xi = panel_nodes(disc.center[pid], disc.angle[pid], disc.axes[pid], k, P, q,
-                                    prm.qbx_nsub)
+        y, ny, wy, xi = panel_nodes(disc.center[pid], disc.angle[pid], disc.axes[pid],
+                                    disc.desc[J], P, q, prm.qbx_nsub)
         L = _sub_interp(q, prm.qbx_nsub)
         d = y - c
         ry = np.hypot(d[:, 0], d[:, 1])
@@ -175,9 +175,9 @@ def oversampled_row(disc, x, J, nsub, gradient=False):
     interpolated sigma."""
     prm = disc.params
     P, q = prm.panels, prm.q
-    pid = J // P
-    k = J - pid * P
-    y, ny, wy, xi = panel_nodes(disc.center[pid], disc.angle[pid], disc.axes[pid], k, P, q, nsub)
+    pid = int(disc.panel_pid[J])
+    y, ny, wy, xi = panel_nodes(disc.center[pid], disc.angle[pid], disc.axes[pid], disc.desc[J], P,
+                                q, nsub)
     L = _sub_interp(q, nsub)
     xx = np.broadcast_to(x, y.shape)
     k = dl_kernel(xx, y, ny, disc.kappa)
