@@ -112,6 +112,20 @@ typedef struct yq_params {
                                   YQ_FAR_DIRECT and single problems (the batch and the server
                                   reject it); the far field then evaluates K0 and K1 at every pair
                                   (FP64, or FP32 for the inner operator of YQ_MIXED) */
+  int32_t refine_levels;       /* adaptive panel refinement near contact (section 5's QBX
+                                  preconditions; the paper refines at most 3-5 levels per time
+                                  step), 0..8, 0 (default): P equal-parameter panels.  Panels
+                                  are parameter intervals 2 pi / P (k + [idx, idx + 1] 2^-lev);
+                                  passes split every panel whose arclength exceeds refine_ratio
+                                  times its distance to the nearest node of another particle,
+                                  at most refine_levels times, then each particle's panels are
+                                  balanced so that the panels a QBX window takes are at most
+                                  one level coarser than the target's.  N then varies per
+                                  particle (yq_num_nodes); node order stays particle, panel
+                                  (increasing t), node.  Single problems only (the batch, the
+                                  server and yq_step reject it) */
+  double refine_ratio;         /* > 0, default 2 (the expansion disk, radius h/4 at
+                                  qbx_radius 0.25, stays its radius away from other particles) */
 } yq_params;
 
 typedef struct yq_solve_info {
@@ -127,7 +141,7 @@ typedef struct yq_solve_info {
  * near_oversample 4, pot_oversample 8, pot_beta 0.5, FP64, direct far field,
  * FMM order 20 / 64 per leaf, tol 1e-10, maxiter 200, restart 100,
  * inner_tol 1e-6, max_refine 8, fmm_resid_order 40, fmm_m2l YQ_M2L_MFMA, cutoff_tol 1e-12,
- * sl_coupling 0. */
+ * sl_coupling 0, refine_levels 0, refine_ratio 2. */
 void yq_default_params(yq_params* params);
 
 /* Creates a problem on the current HIP device.  params: host, copied. */

@@ -59,6 +59,8 @@ class yq_params(ctypes.Structure):
         ("fmm_m2l", c_int32),
         ("cutoff_tol", c_double),
         ("sl_coupling", c_double),
+        ("refine_levels", c_int32),
+        ("refine_ratio", c_double),
     ]
 
 

@@ -9,6 +9,7 @@
 
 #include "common.h"
 #include "problem.h"
+#include "refine.h"
 
 using namespace yq;
 
@@ -96,6 +97,10 @@ void check_params(const yq_params& p) {
              "sl_coupling must be finite and >= 0");
   YQ_REQUIRE(p.sl_coupling == 0.0 || p.far_mode == YQ_FAR_DIRECT, YQ_EINVAL,
              "the combined representation (sl_coupling > 0) needs the direct far field");
+  YQ_REQUIRE(p.refine_levels >= 0 && p.refine_levels <= 8, YQ_EINVAL,
+             "refine_levels out of range 0..8");
+  YQ_REQUIRE(std::isfinite(p.refine_ratio) && p.refine_ratio > 0.0, YQ_EINVAL,
+             "refine_ratio must be finite and > 0");
   YQ_REQUIRE(p.fmm_order >= 1 && p.fmm_order <= MAXP_FMM, YQ_EINVAL, "fmm_order out of range 1..48");
   YQ_REQUIRE(p.fmm_resid_order >= 0 && p.fmm_resid_order <= MAXP_FMM, YQ_EINVAL,
              "fmm_resid_order out of range 0..48");
@@ -424,6 +429,8 @@ void yq_default_params(yq_params* p) {
   p->fmm_m2l = YQ_M2L_MFMA;
   p->cutoff_tol = 1e-12;
   p->sl_coupling = 0.0;
+  p->refine_levels = 0;
+  p->refine_ratio = 2.0;
 }
 
 const char* yq_error_string(int status) {
@@ -508,8 +515,9 @@ void setup_particles(yq_problem* pb, int32_t n, const double* center_xy, const d
   YQ_REQUIRE(n >= 1, YQ_EINVAL, "need at least one particle");
   YQ_REQUIRE(std::isfinite(kappa) && kappa > 0.0, YQ_EINVAL, "kappa must be finite and > 0");
   const int P = pb->prm.panels_per_particle;
-  const int64_t N = (int64_t)n * P * Q;
-  YQ_REQUIRE(N < (int64_t)INT32_MAX, YQ_EINVAL, "too many nodes for one problem");
+  const int levels = pb->batch_member ? 0 : pb->prm.refine_levels;
+  YQ_REQUIRE((int64_t)n * P * Q < (int64_t)INT32_MAX, YQ_EINVAL, "too many nodes for one problem");
+  YQ_REQUIRE(!(rot && levels > 0), YQ_EINVAL, "rigid motion set-up with adaptive refinement");
   double amax = 0.0;
   pb->h_pc.assign((size_t)n * 5, 0.0);
   for (int i = 0; i < n; ++i) {
@@ -532,15 +540,15 @@ void setup_particles(yq_problem* pb, int32_t n, const double* center_xy, const d
   pb->have_f = false;
   const bool had_qbx = pb->qbx_valid;   // W, WGx, WGy hold the current set-up's correction
   pb->qbx_valid = false;
-  pb->n = n;
-  pb->N = N;
-  pb->kappa = kappa;
   hipStream_t s = pb->stream;
 
   // particle neighbour lists (host): every particle whose ellipse could hold
-  // a near panel of, or overlap, particle p; p itself is included.
-  const double margin = std::max(pb->prm.near_beta, pb->prm.pot_beta) * 2.0 * PI * amax / P *
-                            1.01 + 1e-9;
+  // a near panel of, or overlap, particle p, or (with refinement) come closer
+  // than the longest panel / refine_ratio to it; p itself is included.  A panel's
+  // arclength is at most 2 pi A / P.
+  double reach = std::max(pb->prm.near_beta, pb->prm.pot_beta);
+  if (levels > 0) reach = std::max(reach, 1.0 / pb->prm.refine_ratio);
+  const double margin = reach * 2.0 * PI * amax / P * 1.01 + 1e-9;
   // Candidates come from a uniform grid of cell side 2 amax + margin (no pair
   // closer than that can be missed); each list is ascending in q.
   std::vector<int> nbp(n + 1, 0), nbi;
@@ -589,22 +597,56 @@ void setup_particles(yq_problem* pb, int32_t n, const double* center_xy, const d
       nbp[p + 1] = (int)nbi.size();
     }
   }
+  // adaptive panels near contact (host, FP64): the panel table (particle, base
+  // panel, level, index) in node order and every particle's first panel
+  std::vector<int4> ptab;
+  std::vector<int> poff;
+  if (levels > 0) {
+    const auto pans = refine_panels(pb->h_pc.data(), n, P, levels, pb->prm.refine_ratio,
+                                    pb->prm.qbx_window, pb->consts.xg, pb->consts.wg, Q, nbp, nbi);
+    poff.assign(n + 1, 0);
+    for (int i = 0; i < n; ++i) {
+      YQ_REQUIRE((int64_t)poff[i] + (int64_t)pans[i].size() < (int64_t)INT32_MAX / Q, YQ_EINVAL,
+                 "too many refined panels for one problem");
+      poff[i + 1] = poff[i] + (int)pans[i].size();
+      for (const PanelDesc& d : pans[i]) ptab.push_back(make_int4(i, d.k, d.lev, d.idx));
+    }
+  }
+  const int64_t npan = levels > 0 ? (int64_t)poff[n] : (int64_t)n * P;
+  const int64_t N = npan * Q;
+  pb->n = n;
+  pb->N = N;
+  pb->npan = npan;
+  pb->refined = levels > 0;
+  pb->kappa = kappa;
+
   // host inputs go through pinned staging, so their copies are asynchronous; all
   // of them complete before the geometry check below returns
   {
     const size_t b_pc = pb->h_pc.size() * sizeof(double);
     const size_t b_np = nbp.size() * sizeof(int), b_ni = nbi.size() * sizeof(int);
-    pb->stage.fit(b_pc + b_np + b_ni + 16);
+    const size_t b_pt = ptab.size() * sizeof(int4), b_po = poff.size() * sizeof(int);
+    // the panel table starts on a 16-byte boundary
+    const size_t o_pt = (b_pc + b_np + b_ni + 15) / 16 * 16, o_po = o_pt + b_pt;
+    pb->stage.fit(o_po + b_po + 16);
     char* st = pb->stage.p;
     std::memcpy(st, pb->h_pc.data(), b_pc);
     std::memcpy(st + b_pc, nbp.data(), b_np);
     if (b_ni) std::memcpy(st + b_pc + b_np, nbi.data(), b_ni);
+    if (b_pt) std::memcpy(st + o_pt, ptab.data(), b_pt);
+    if (b_po) std::memcpy(st + o_po, poff.data(), b_po);
     pb->pc.fit(pb->h_pc.size());
     pb->nb_ptr.fit(nbp.size());
     pb->nb_idx.fit(std::max<size_t>(nbi.size(), 1));
     YQ_HIP(hipMemcpyAsync(pb->pc.p, st, b_pc, hipMemcpyHostToDevice, s));
     YQ_HIP(hipMemcpyAsync(pb->nb_ptr.p, st + b_pc, b_np, hipMemcpyHostToDevice, s));
     if (b_ni) YQ_HIP(hipMemcpyAsync(pb->nb_idx.p, st + b_pc + b_np, b_ni, hipMemcpyHostToDevice, s));
+    if (levels > 0) {
+      pb->pan.fit(ptab.size());
+      pb->poff.fit(poff.size());
+      YQ_HIP(hipMemcpyAsync(pb->pan.p, st + o_pt, b_pt, hipMemcpyHostToDevice, s));
+      YQ_HIP(hipMemcpyAsync(pb->poff.p, st + o_po, b_po, hipMemcpyHostToDevice, s));
+    }
   }
 
   // a1: nodes, normals, weights; panel arclengths and bounding circles
@@ -615,10 +657,10 @@ void setup_particles(yq_problem* pb, int32_t n, const double* center_xy, const d
   pb->w.alloc(N);
   pb->wnx.alloc(N);
   pb->wny.alloc(N);
-  pb->panel_h.alloc((size_t)n * P);
-  pb->pcx.alloc((size_t)n * P);
-  pb->pcy.alloc((size_t)n * P);
-  pb->pr.alloc((size_t)n * P);
+  pb->panel_h.alloc((size_t)npan);
+  pb->pcx.alloc((size_t)npan);
+  pb->pcy.alloc((size_t)npan);
+  pb->pr.alloc((size_t)npan);
   GeomView g = pb->view();
   launch_geometry(g, pb->consts, pb->x.p, pb->y.p, pb->nx.p, pb->ny.p, pb->w.p, pb->wnx.p,
                   pb->wny.p, s);
@@ -1089,7 +1131,7 @@ int yq_eval_potential(yq_problem* pb, const double* sigma, int64_t M, const doub
     YQ_REQUIRE(M >= 0, YQ_EINVAL, "M < 0");
     if (M == 0) return;
     YQ_REQUIRE(sigma && tx && ty && u, YQ_EINVAL, "null argument");
-    const int64_t npan = (int64_t)pb->n * pb->prm.panels_per_particle;
+    const int64_t npan = pb->npan;
     PotPlan pp = pot_plan(M, npan);
     pb->pot_partial.reserve((size_t)pp.chunks * M);
     const int nsub = pb->prm.pot_oversample;
@@ -1212,6 +1254,8 @@ int yq_step(yq_problem* pb, const yq_dynamics* dyn, double* sigma, double* sigma
     require_ready(pb);
     YQ_REQUIRE(dyn && sigma, YQ_EINVAL, "null argument");
     YQ_REQUIRE(sigma_prev != sigma, YQ_EINVAL, "sigma_prev aliases sigma");
+    YQ_REQUIRE(pb->prm.refine_levels == 0, YQ_EINVAL,
+               "time steps keep the nodes in each particle's frame: no adaptive refinement");
     YQ_REQUIRE(pb->have_f, YQ_ESTATE, "boundary data not set");
     YQ_REQUIRE(std::isfinite(dyn->dt) && dyn->dt >= 0.0, YQ_EINVAL, "dt must be finite and >= 0");
     YQ_REQUIRE(std::isfinite(dyn->xi_x) && dyn->xi_x > 0.0 && std::isfinite(dyn->xi_theta) &&

@@ -100,6 +100,8 @@ int yq_batch_create(const yq_params* params, yq_batch** out) {
                "the cutoff far field is available to single problems only");
     YQ_REQUIRE(params->sl_coupling == 0.0, YQ_EINVAL,
                "the combined representation (sl_coupling > 0) is available to single problems only");
+    YQ_REQUIRE(params->refine_levels == 0, YQ_EINVAL,
+               "adaptive panel refinement is available to single problems only");
     auto b = std::make_unique<yq_batch>();
     b->prm = *params;
     b->eng.init(*params);

@@ -198,7 +198,69 @@ struct GeomView {
   // combined representation D + eta S (eq. bwform): coupling of the single layer,
   // 0 for the double layer alone
   double eta = 0.0;
+  // adaptive panels (null: P equal-parameter panels per particle, panel J =
+  // particle * P + k): per panel (particle, base panel k, level, index at that
+  // level), and the first panel of every particle [n + 1]; npan panels in all
+  const int4* pan = nullptr;
+  const int* poff = nullptr;
+  int64_t npan = 0;
 };
+
+// ---- panels of a geometry (uniform or adaptively refined) -----------------------------
+
+__device__ __forceinline__ int panel_particle(const GeomView& g, int64_t J) {
+  return g.pan ? g.pan[J].x : (int)(J / g.P);
+}
+
+// The panels of particle p: [first, first + cnt), in increasing parameter.
+__device__ __forceinline__ void particle_panels(const GeomView& g, int p, int64_t& first,
+                                                int& cnt) {
+  if (g.poff) {
+    first = g.poff[p];
+    cnt = g.poff[p + 1] - g.poff[p];
+  } else {
+    first = (int64_t)p * g.P;
+    cnt = g.P;
+  }
+}
+
+// Panel J's place on its particle's ring: the ring's first panel, its length,
+// and J - first.
+struct Ring {
+  int64_t first;
+  int cnt, k;
+};
+
+__device__ __forceinline__ Ring ring_of(const GeomView& g, int64_t J) {
+  Ring r;
+  particle_panels(g, panel_particle(g, J), r.first, r.cnt);
+  r.k = (int)(J - r.first);
+  return r;
+}
+
+// The panel o places from the ring position r (|o| < r.cnt).
+__device__ __forceinline__ int64_t ring_step(const Ring& r, int o) {
+  int kj = (r.k + o) % r.cnt;
+  if (kj < 0) kj += r.cnt;
+  return r.first + kj;
+}
+
+// Parameter t of panel J at coordinate xi in [-1, 1], and dt / dxi: panel J is
+// 2 pi / P (k + [idx, idx + 1] 2^-lev) of base panel k of its ellipse.
+__device__ __forceinline__ double panel_param(const GeomView& g, int64_t J, double xi,
+                                              double& dt) {
+  int k, lev = 0, idx = 0;
+  if (g.pan) {
+    const int4 d = g.pan[J];
+    k = d.y;
+    lev = d.z;
+    idx = d.w;
+  } else {
+    k = (int)(J % g.P);
+  }
+  dt = ldexp(PI / g.P, -lev);
+  return 2.0 * PI / g.P * (k + ldexp(idx + 0.5 * (xi + 1.0), -lev));
+}
 
 // Discretisation constants, passed to kernels by value.
 struct Consts {

@@ -322,15 +322,10 @@ __global__ __launch_bounds__(256) void finish_kernel(GeomView g, int win, int ch
   }
   double corr = 0.0;
   if (win >= 0) {
-    const int P = g.P;
-    const int64_t pan = i / Q;
-    const int64_t pid = pan / P;
-    const int k = (int)(pan % P);
+    const Ring rg = ring_of(g, i / Q);
     const int m0 = 2 * q;
     for (int sl = 0; sl <= 2 * win; ++sl) {
-      int kj = (k + sl - win) % P;
-      if (kj < 0) kj += P;
-      const double* sg = sigma + (pid * P + kj) * Q + m0;
+      const double* sg = sigma + ring_step(rg, sl - win) * Q + m0;
       const double* wr = W + ((int64_t)sl * Q + m0) * N + i;
       corr = fma(wr[0], sg[0], corr);
       corr = fma(wr[N], sg[1], corr);
@@ -366,14 +361,9 @@ __global__ void finish_grad_kernel(GeomView g, int win, int chunks, const double
   const double sc = g.kappa * g.kappa / (2.0 * PI);
   sx *= sc;
   sy *= sc;
-  const int P = g.P;
-  const int64_t pan = i / Q;
-  const int64_t pid = pan / P;
-  const int k = (int)(pan % P);
+  const Ring rg = ring_of(g, i / Q);
   for (int sl = 0; sl <= 2 * win; ++sl) {
-    int kj = (k + sl - win) % P;
-    if (kj < 0) kj += P;
-    const double* sg = sigma + (pid * P + kj) * Q;
+    const double* sg = sigma + ring_step(rg, sl - win) * Q;
     const double* wx = WGx + (int64_t)sl * Q * N + i;
     const double* wy = WGy + (int64_t)sl * Q * N + i;
 #pragma unroll

@@ -100,12 +100,12 @@ __global__ void geometry_kernel(GeomView g, Consts c, double* __restrict__ x, do
   if (i >= g.N) return;
   int m = (int)(i % Q);
   int64_t pan = i / Q;
-  int p = (int)(pan / g.P);
-  int k = (int)(pan % g.P);
-  double t = 2.0 * PI / g.P * (k + 0.5 * (c.xg[m] + 1.0));
+  int p = panel_particle(g, pan);
+  double dt;
+  double t = panel_param(g, pan, c.xg[m], dt);
   double px, py, nxo, nyo, sp;
   ellipse_point(g.pc + 5 * p, t, px, py, nxo, nyo, sp);
-  double ww = (PI / g.P) * c.wg[m] * sp;
+  double ww = dt * c.wg[m] * sp;
   x[i] = px;
   y[i] = py;
   nx[i] = nxo;
@@ -120,7 +120,7 @@ __global__ void geometry_kernel(GeomView g, Consts c, double* __restrict__ x, do
 __global__ void panel_stats_kernel(GeomView g, double* __restrict__ h, double* __restrict__ pcx,
                                    double* __restrict__ pcy, double* __restrict__ pr) {
   int64_t J = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (J >= (int64_t)g.n * g.P) return;
+  if (J >= g.npan) return;
   const int64_t b = J * Q;
   double s = 0.0, mx = 0.0, my = 0.0;
   for (int m = 0; m < Q; ++m) {
@@ -144,7 +144,7 @@ __global__ void panel_stats_kernel(GeomView g, double* __restrict__ h, double* _
 __global__ void label_kernel(GeomView g, int kind, double a, double b, double* __restrict__ f) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= g.N) return;
-  int p = (int)(i / ((int64_t)g.P * Q));
+  int p = panel_particle(g, i / Q);
   const double* pp = g.pc + 5 * p;
   double sa, ca;
   sincos(pp[2], &sa, &ca);
@@ -172,7 +172,7 @@ __global__ void geom_check_kernel(GeomView g, const int* __restrict__ nb_ptr,
                                   const int* __restrict__ nb_idx, int* bad) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= g.N) return;
-  int p = (int)(i / ((int64_t)g.P * Q));
+  int p = panel_particle(g, i / Q);
   double xi = g.x[i], yi = g.y[i];
   for (int e = nb_ptr[p]; e < nb_ptr[p + 1]; ++e) {
     int q = nb_idx[e];
@@ -194,23 +194,28 @@ __global__ void near_kernel(GeomView g, int win, double beta, const int* __restr
                             const int* __restrict__ offs) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= g.N) return;
-  const int P = g.P;
   int64_t pan = i / Q;
-  int p = (int)(pan / P);
-  int k = (int)(pan % P);
+  int p = panel_particle(g, pan);
+  int64_t pfirst;
+  int pcnt;
+  particle_panels(g, p, pfirst, pcnt);
+  int k = (int)(pan - pfirst);
   double xi = g.x[i], yi = g.y[i];
   int cnt = 0;
   int base = offs ? offs[i] : 0;
   for (int e = nb_ptr[p]; e < nb_ptr[p + 1]; ++e) {
     int q = nb_idx[e];
-    for (int kk = 0; kk < P; ++kk) {
+    int64_t qfirst;
+    int qcnt;
+    particle_panels(g, q, qfirst, qcnt);
+    for (int kk = 0; kk < qcnt; ++kk) {
       if (q == p) {
         int dk = kk - k;
         if (dk < 0) dk = -dk;
-        if (dk > P - dk) dk = P - dk;  // circular distance
+        if (dk > qcnt - dk) dk = qcnt - dk;  // circular distance along the ring
         if (dk <= win) continue;
       }
-      int64_t J = (int64_t)q * P + kk;
+      int64_t J = qfirst + kk;
       double bh = beta * g.panel_h[J];
       double dx = xi - pcx[J], dy = yi - pcy[J];
       double dc = sqrt(dx * dx + dy * dy) - pr[J];
@@ -239,7 +244,7 @@ void launch_geometry(const GeomView& g, const Consts& c, double* x, double* y, d
 
 void launch_panel_stats(const GeomView& g, double* panel_h, double* pcx, double* pcy, double* pr,
                         hipStream_t s) {
-  panel_stats_kernel<<<nblk((int64_t)g.n * g.P, 256), 256, 0, s>>>(g, panel_h, pcx, pcy, pr);
+  panel_stats_kernel<<<nblk(g.npan, 256), 256, 0, s>>>(g, panel_h, pcx, pcy, pr);
   YQ_HIP(hipGetLastError());
 }
 

@@ -34,8 +34,11 @@ __global__ __launch_bounds__(FB) void forces_kernel(GeomView g, const double* __
                                                     double* __restrict__ energy) {
   __shared__ double sh[FB];
   const int p = blockIdx.x;
-  const int64_t b = (int64_t)p * g.P * Q;
-  const int64_t e = b + (int64_t)g.P * Q;
+  int64_t first;
+  int cnt;
+  particle_panels(g, p, first, cnt);
+  const int64_t b = first * Q;
+  const int64_t e = b + (int64_t)cnt * Q;
   const double cx = g.pc[5 * p], cy = g.pc[5 * p + 1];
   const double kap = g.kappa;
   double fx = 0.0, fy = 0.0, tq = 0.0, en = 0.0;
@@ -89,23 +92,24 @@ __global__ void pot_fine_kernel(GeomView g, Consts c, int nsub, double* __restri
                                 double* __restrict__ fwy) {
   const int F = nsub * Q;
   const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (idx >= (int64_t)g.n * g.P * F) return;
+  if (idx >= g.npan * F) return;
   const int64_t J = idx / F;
   const int k = (int)(idx - J * F);
   const int sub = k / Q, gq = k - sub * Q;
-  const int pid = (int)(J / g.P), kj = (int)(J % g.P);
+  const int pid = panel_particle(g, J);
   const double* pp = g.pc + 5 * pid;
   double sa, ca;
   sincos(pp[2], &sa, &ca);
   const double xl = -1.0 + (2.0 * sub + c.xg[gq] + 1.0) / nsub;
-  const double t = 2.0 * PI / g.P * (kj + 0.5 * (xl + 1.0));
+  double dt;
+  const double t = panel_param(g, J, xl, dt);
   double st, ct;
   sincos(t, &st, &ct);
   const double ex = pp[3] * ct, ey = pp[4] * st;
   const double ddx = -pp[3] * st, ddy = pp[4] * ct;
   const double gx = ca * ddx - sa * ddy, gy = sa * ddx + ca * ddy;
-  // w / |gamma'| = (pi / P / nsub) wg, so (w nu) = (pi / P / nsub) wg (gy, -gx)
-  const double wq = (PI / g.P / nsub) * c.wg[gq];
+  // w / |gamma'| = (dt / nsub) wg, so (w nu) = (dt / nsub) wg (gy, -gx)
+  const double wq = (dt / nsub) * c.wg[gq];
   fx[idx] = pp[0] + ca * ex - sa * ey;
   fy[idx] = pp[1] + sa * ex + ca * ey;
   fwx[idx] = wq * gy;
@@ -139,7 +143,7 @@ __global__ __launch_bounds__(64) void potential_kernel(GeomView g, PotFine pf, d
   const int64_t a = active ? a0 : 0;
   const double zx = tx[a], zy = ty[a];
   const double kap2 = g.kappa * g.kappa;
-  const int64_t npan = (int64_t)g.n * g.P;
+  const int64_t npan = g.npan;
   const int64_t J0 = (int64_t)blockIdx.y * per;
   const int64_t J1 = min(npan, J0 + per);
   const int F = pf.nsub * Q;
@@ -261,7 +265,7 @@ void launch_forces(const GeomView& g, const double* f, const double* gx, const d
 
 void launch_pot_fine(const GeomView& g, const Consts& c, int nsub, const PotFine& pf,
                      hipStream_t s) {
-  const int64_t n = (int64_t)g.n * g.P * nsub * Q;
+  const int64_t n = g.npan * nsub * Q;
   if (n == 0) return;
   pot_fine_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(g, c, nsub, pf.x, pf.y, pf.wx, pf.wy);
   YQ_HIP(hipGetLastError());
@@ -271,7 +275,7 @@ void launch_potential(const GeomView& g, const PotFine& pf, const double* L, dou
                       const double* sigma, int64_t M, const double* tx, const double* ty,
                       const PotPlan& pp, double* partial, double* u, hipStream_t s) {
   if (M == 0) return;
-  const int64_t npan = (int64_t)g.n * g.P;
+  const int64_t npan = g.npan;
   const int64_t nf = npan * pf.nsub * Q;
   pot_fine_sigma_kernel<<<(unsigned)((nf + 255) / 256), 256, 0, s>>>(npan, pf.nsub, L, sigma,
                                                                       pf.s);

@@ -64,7 +64,7 @@ extern "C" int yq_eval_potential_noalloc(yq_problem* pb, const double* sigma, in
     YQ_REQUIRE(M >= 0, YQ_EINVAL, "M < 0");
     if (M == 0) return YQ_OK;
     YQ_REQUIRE(sigma && tx && ty && u, YQ_EINVAL, "null argument");
-    const int64_t npan = (int64_t)pb->n * pb->prm.panels_per_particle;
+    const int64_t npan = pb->npan;
     const int nsub = pb->prm.pot_oversample;
     const size_t need = noalloc_potential_bytes(M, npan, nsub);
     YQ_REQUIRE(need <= kNoAllocScratchBytes, YQ_EINVAL,

@@ -17,6 +17,8 @@ struct yq_problem {
 
   int n = 0;
   int64_t N = 0;
+  int64_t npan = 0;   // panels (n * P unless refined)
+  bool refined = false;   // pan / poff describe the panels (adaptive refinement)
   double kappa = 0.0;
   bool ready = false;
   bool have_f = false;
@@ -40,6 +42,8 @@ struct yq_problem {
   DevBuf<double> qfx, qfy, qfwx, qfwy;         // oversampled points of the QBX build
   bool pot_fine_ready = false;                // pf* hold this geometry's points
   DevBuf<int> nb_ptr, nb_idx, bad, ncnt;
+  DevBuf<int4> pan;   // refined panels: (particle, base panel, level, index)
+  DevBuf<int> poff;   // refined panels: first panel of every particle [n + 1]
   DevBuf<int> xrow, xpan;
   int64_t x_total = 0;
   DevBuf<double> xvals, xgvals;
@@ -149,6 +153,11 @@ struct yq_problem {
     g.zcut = zcut64;
     g.zcut_g = zcut64g;
     g.eta = prm.sl_coupling;
+    g.npan = npan;
+    if (refined) {
+      g.pan = pan.p;
+      g.poff = poff.p;
+    }
     return g;
   }
 };

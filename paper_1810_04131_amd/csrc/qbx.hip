@@ -69,12 +69,9 @@ __global__ __launch_bounds__(BS) void qbx_build_kernel(GeomView g, int p, int wi
   const bool active = i0 < g.N;
   const int64_t i = active ? i0 : 0;
   const int slot = blockIdx.y;
-  const int P = g.P;
   const double kap = g.kappa;
 
   const int64_t pan = i / Q;
-  const int pid = (int)(pan / P);
-  const int k = (int)(pan % P);
   const double xi = g.x[i], yi = g.y[i], nxi = g.nx[i], nyi = g.ny[i];
   const double r = radius * g.panel_h[pan];
   const double ir = rcp64(r);
@@ -96,10 +93,9 @@ __global__ __launch_bounds__(BS) void qbx_build_kernel(GeomView g, int p, int wi
     }
   }
 
-  int kj = (k + slot - win) % P;
-  if (kj < 0) kj += P;
+  const int64_t J = ring_step(ring_of(g, pan), slot - win);
   const int F = nsub * Q;
-  const int64_t fbase = ((int64_t)pid * P + kj) * F;
+  const int64_t fbase = J * F;
 
   double acc[Q], agx[Q], agy[Q];
 #pragma unroll
@@ -178,7 +174,7 @@ __global__ __launch_bounds__(BS) void qbx_build_kernel(GeomView g, int p, int wi
     }
   }
 
-  const int64_t jb = ((int64_t)pid * P + kj) * Q;
+  const int64_t jb = J * Q;
 #pragma unroll
   for (int m = 0; m < Q; ++m) {
     const int64_t j = jb + m;
@@ -217,14 +213,15 @@ __global__ void near_rows_kernel(GeomView g, Consts c, int nsub, const double* _
   const double cst = kap2 / (2.0 * PI);
   for (int e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
     const int J = panels[e];
-    const int pid = J / g.P, kj = J % g.P;
+    const int pid = panel_particle(g, J);
     const double* pp = g.pc + 5 * pid;
     double acc[Q], agx[Q], agy[Q];
     for (int m = 0; m < Q; ++m) acc[m] = agx[m] = agy[m] = 0.0;
     for (int sub = 0; sub < nsub; ++sub) {
       for (int gq = 0; gq < Q; ++gq) {
         const double xl = -1.0 + (2.0 * sub + c.xg[gq] + 1.0) / nsub;
-        const double t = 2.0 * PI / g.P * (kj + 0.5 * (xl + 1.0));
+        double dt;
+        const double t = panel_param(g, J, xl, dt);
         double st, ct, sa, ca;
         sincos(t, &st, &ct);
         sincos(pp[2], &sa, &ca);
@@ -234,7 +231,7 @@ __global__ void near_rows_kernel(GeomView g, Consts c, int nsub, const double* _
         const double yfy = pp[1] + sa * ex + ca * ey;
         const double gx = ca * ddx - sa * ddy, gy = sa * ddx + ca * ddy;
         const double sp = sqrt(gx * gx + gy * gy);
-        const double wf = (PI / g.P / nsub) * c.wg[gq] * sp;
+        const double wf = (dt / nsub) * c.wg[gq] * sp;
         const double qx = wf * gy / sp, qy = -wf * gx / sp;
         const double dx = xi - yfx, dy = yi - yfy;
         const double r2 = dx * dx + dy * dy;

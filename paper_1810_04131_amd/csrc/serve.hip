@@ -329,6 +329,8 @@ int yq_server_create(const yq_params* params, int64_t node_capacity, int32_t max
                "the cutoff far field is available to single problems only");
     YQ_REQUIRE(params->sl_coupling == 0.0, YQ_EINVAL,
                "the combined representation (sl_coupling > 0) is available to single problems only");
+    YQ_REQUIRE(params->refine_levels == 0, YQ_EINVAL,
+               "adaptive panel refinement is available to single problems only");
     auto s = std::make_unique<yq_server>();
     s->prm = *params;
     s->capacity = node_capacity;
