@@ -138,7 +138,7 @@ def parse():
     ap.add_argument("--rate", type=float, default=200.0, help="serve: arrival rate (1/s)")
     ap.add_argument("--nmax", type=int, default=None,
                     help="batch/serve: largest particle count (default 200 batch, 2000 serve)")
-    ap.add_argument("--fmm-workers", type=int, default=3,
+    ap.add_argument("--fmm-workers", type=int, default=6,
                     help="serve/batch: FMM-lane worker threads")
     ap.add_argument("--batch-lane", choices=["hybrid", "fused", "engine"], default="hybrid",
                     help="batch: hybrid = configurations from --fmm-min-nodes on take the FMM "

@@ -333,9 +333,9 @@ int yq_get_particles(const yq_problem* prob, double* center_xy, double* angle);
  * FMM lane: configurations of at least a threshold node count (params->far_mode
  * YQ_FAR_FMM: all; YQ_FAR_AUTO: 20000 nodes; YQ_FAR_DIRECT: none;
  * yq_batch_set_fmm overrides) are not engine members: each is a standalone
- * problem with the FMM far field, solved by worker threads (largest first, one
- * stream of default priority each) while the engine solves the rest; the
- * engine then launches its iteration eagerly instead of replaying a graph.
+ * problem with the FMM far field, solved (and its forces evaluated) by worker
+ * threads (default 6, largest first from a shared queue, one stream of default
+ * priority each) while the engine replays its iteration graph for the rest.
  * The batch owns a HIP stream of default priority; every batch call is
  * synchronous (returns after its work is done) and reads its device inputs when
  * called, so the caller must have finished writing them. */
@@ -373,7 +373,8 @@ int yq_batch_apply_operator(yq_batch* batch, const double* sigma, double* out, i
 int yq_batch_solve(yq_batch* batch, double* sigma, yq_solve_info* info);
 
 /* Forces and torques of every particle (particles in batch order): dev force
- * [2 * total particles], dev torque [total particles]; host energy [nconf]. */
+ * [2 * total particles], dev torque [total particles]; host energy [nconf].
+ * The FMM lane's configurations run on the worker threads beside the engine's. */
 int yq_batch_forces(yq_batch* batch, const double* sigma, double gamma, double* force,
                     double* torque, double* energy);
 

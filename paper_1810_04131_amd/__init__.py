@@ -276,7 +276,7 @@ class Batch:
     def _sync(self):
         self.torch.cuda.synchronize(self.device)
 
-    def set_fmm(self, min_nodes, workers=3):
+    def set_fmm(self, min_nodes, workers=6):
         """Configurations of at least min_nodes nodes take the FMM lane (before set_configs)."""
         self._check(self.lib.yq_batch_set_fmm(self.h, int(min_nodes), int(workers)))
         return self

@@ -31,7 +31,7 @@ struct yq_batch {
   bool have_f = false;
   // FMM lane
   int64_t fmm_min_nodes = std::numeric_limits<int64_t>::max();
-  int fmm_workers = 3;
+  int fmm_workers = 6;
   std::vector<int> direct_idx, fmm_idx;   // configuration indices of each lane
   std::vector<hipStream_t> streams;       // one per worker (default priority)
   int device = 0;
@@ -72,6 +72,38 @@ void require(const yq_batch* b) {
 // returns with its work done, so a later solve on a worker stream sees it).
 void sync_lane(yq_batch* b) {
   for (int c : b->fmm_idx) YQ_HIP(hipStreamSynchronize(b->probs[c]->stream));
+}
+
+// Runs job(c, pb) for every FMM-lane configuration c on the worker threads
+// (largest first, from a shared queue), each problem on its worker's stream, while
+// local() runs the fused engine's part on this thread; then waits for the workers
+// and raises the first lane failure (codes other than YQ_OK and YQ_ENOCONV).
+template <class Job, class Local>
+void run_lane(yq_batch* b, Job&& job, Local&& local) {
+  const int nf = (int)b->fmm_idx.size();
+  std::vector<int> codes(nf, YQ_OK);
+  std::vector<std::string> errs(nf);
+  std::atomic<int> next{0};
+  {
+    std::vector<std::unique_ptr<HostThread>> workers;   // joined on every exit path
+    for (size_t w = 0; w < b->streams.size() && nf > 0; ++w) {
+      workers.push_back(std::make_unique<HostThread>([&, w] {
+        (void)hipSetDevice(b->device);
+        for (int k = next++; k < nf; k = next++) {
+          const int c = b->fmm_idx[k];
+          yq_problem* pb = b->probs[c].get();
+          pb->stream = b->streams[w];   // earlier work on its stream is done (sync_lane)
+          const int st = job(c, pb);
+          codes[k] = st;
+          if (st != YQ_OK && st != YQ_ENOCONV) errs[k] = yq_last_error(pb);
+        }
+      }));
+    }
+    local();
+  }
+  for (int k = 0; k < nf; ++k)
+    YQ_REQUIRE(codes[k] == YQ_OK || codes[k] == YQ_ENOCONV, codes[k],
+               "configuration " + std::to_string(b->fmm_idx[k]) + ": " + errs[k]);
 }
 
 void rebuild_plans(yq_batch* b) {
@@ -251,39 +283,21 @@ int yq_batch_solve(yq_batch* b, double* sigma, yq_solve_info* info) {
     YQ_REQUIRE(b->have_f, YQ_ESTATE, "boundary data not set");
     const int nconf = (int)b->probs.size();
     std::vector<yq_solve_info> all(nconf);
-    // FMM lane on worker threads
-    const int nf = (int)b->fmm_idx.size();
-    std::vector<int> codes(nf, YQ_OK);
-    std::vector<std::string> errs(nf);
-    std::atomic<int> next{0};
     // the fused iteration's graphs are captured before any worker starts, so no
     // capture overlaps the workers' allocations
     if (!b->direct_idx.empty()) b->eng.ensure_graphs();
-    std::vector<std::unique_ptr<HostThread>> workers;
-    for (size_t w = 0; w < b->streams.size() && nf > 0; ++w) {
-      workers.push_back(std::make_unique<HostThread>([&, w] {
-        (void)hipSetDevice(b->device);
-        for (int k = next++; k < nf; k = next++) {
-          const int c = b->fmm_idx[k];
-          yq_problem* pb = b->probs[c].get();
-          pb->stream = b->streams[w];   // earlier work on its stream is done (sync_lane)
-          const int st = yq_solve(pb, nullptr, sigma + b->offsets[c], &all[c]);
-          codes[k] = st;
-          if (st != YQ_OK && st != YQ_ENOCONV) errs[k] = yq_last_error(pb);
-        }
-      }));
-    }
-    // fused lane on this thread
-    if (!b->direct_idx.empty()) {
-      std::vector<yq_solve_info> inf;
-      b->eng.solve(inf, sigma);
-      YQ_HIP(hipStreamSynchronize(b->eng.stream));
-      for (size_t k = 0; k < inf.size(); ++k) all[b->direct_idx[k]] = inf[k];
-    }
-    for (auto& x : workers) x->join();
-    for (int k = 0; k < nf; ++k)
-      YQ_REQUIRE(codes[k] == YQ_OK || codes[k] == YQ_ENOCONV, codes[k],
-                 "configuration " + std::to_string(b->fmm_idx[k]) + ": " + errs[k]);
+    run_lane(
+        b,
+        [&](int c, yq_problem* pb) {
+          return yq_solve(pb, nullptr, sigma + b->offsets[c], &all[c]);
+        },
+        [&] {   // fused lane on this thread
+          if (b->direct_idx.empty()) return;
+          std::vector<yq_solve_info> inf;
+          b->eng.solve(inf, sigma);
+          YQ_HIP(hipStreamSynchronize(b->eng.stream));
+          for (size_t k = 0; k < inf.size(); ++k) all[b->direct_idx[k]] = inf[k];
+        });
     for (int c = 0; c < nconf; ++c) {
       if (info) info[c] = all[c];
       if (!(all[c].residual <= b->prm.tol)) status = YQ_ENOCONV;
@@ -300,13 +314,21 @@ int yq_batch_forces(yq_batch* b, const double* sigma, double gamma, double* forc
     require(b);
     YQ_REQUIRE(b->have_f, YQ_ESTATE, "boundary data not set");
     YQ_REQUIRE(sigma && force && torque, YQ_EINVAL, "null argument");
-    for (size_t c = 0; c < b->probs.size(); ++c) {
-      double e = 0.0;
-      int st = yq_forces(b->probs[c].get(), sigma + b->offsets[c], gamma,
-                         force + 2 * b->poffsets[c], torque + b->poffsets[c], &e);
-      YQ_REQUIRE(st == YQ_OK, st, yq_last_error(b->probs[c].get()));
-      if (energy) energy[c] = e;
-    }
+    std::vector<double> en(b->probs.size(), 0.0);
+    auto one = [&](int c, yq_problem* pb) {
+      return yq_forces(pb, sigma + b->offsets[c], gamma, force + 2 * b->poffsets[c],
+                       torque + b->poffsets[c], &en[c]);
+    };
+    // the FMM lane's gradient passes on the worker threads, the direct members' here
+    run_lane(b, one, [&] {
+      for (int c : b->direct_idx) {
+        yq_problem* pb = b->probs[c].get();
+        const int st = one(c, pb);
+        YQ_REQUIRE(st == YQ_OK, st, yq_last_error(pb));
+      }
+    });
+    if (energy)
+      for (size_t c = 0; c < en.size(); ++c) energy[c] = en[c];
   });
 }
 
