@@ -140,12 +140,13 @@ def parse():
                     help="batch/serve: largest particle count (default 200 batch, 2000 serve)")
     ap.add_argument("--fmm-workers", type=int, default=6,
                     help="serve/batch: FMM-lane worker threads")
-    ap.add_argument("--batch-lane", choices=["hybrid", "fused", "engine"], default="hybrid",
-                    help="batch: hybrid = configurations from --fmm-min-nodes on take the FMM "
-                         "lane; fused = every configuration in the fused direct engine; engine "
-                         "= only the configurations below --fmm-min-nodes (the fused engine's "
-                         "members of the hybrid run, without the lane's worker threads: the "
-                         "command for counter runs of the fused kernels)")
+    ap.add_argument("--batch-lane", choices=["hybrid", "lane", "fused", "engine"], default="hybrid",
+                    help="batch: hybrid = configurations from --fmm-min-nodes on take the FMM as "
+                         "trees of the engine's forest (one captured iteration for the whole "
+                         "batch); lane = they are standalone FMM problems solved by worker "
+                         "threads beside the engine; fused = every configuration in the fused "
+                         "direct engine; engine = only the configurations below "
+                         "--fmm-min-nodes (the direct members of the hybrid run)")
     ap.add_argument("--fmm-min-nodes", type=int, default=20000,
                     help="serve: requests of at least this many nodes take the FMM lane")
     ap.add_argument("--fp64-requests", type=int, default=None,
@@ -396,20 +397,21 @@ def bench_batch(args):
     engine_only = args.batch_lane == "engine"
     if engine_only:
         cfgs = [c for c in cfgs if c.n * 512 < args.fmm_min_nodes]
-    hybrid = args.batch_lane == "hybrid"
+    hybrid = args.batch_lane in ("hybrid", "lane")
+    forest = args.batch_lane == "hybrid"
     thr = args.fmm_min_nodes if hybrid else None
     tol = args.tol
     prm = yq.default_params(panels_per_particle=32, qbx_order=10, tol=tol,
                             precision=yq.YQ_MIXED, restart=60, maxiter=300)
     b = yq.Batch(prm)
     if hybrid:
-        b.set_fmm(thr, workers=args.fmm_workers)
+        b.set_fmm(thr, workers=args.fmm_workers, in_engine=forest)
     t0 = time.perf_counter()
     b.set_configs(cfgs)
     t_setup = time.perf_counter() - t0
     N = np.diff(b.offsets).astype(float)
     lane = N >= thr if hybrid else np.zeros(len(cfgs), dtype=bool)
-    log(f"set-up {t_setup:.1f} s, {b.total} nodes, {int(lane.sum())} configurations in the FMM lane")
+    log(f"set-up {t_setup:.1f} s, {b.total} nodes, {int(lane.sum())} configurations take the FMM")
     pblk, fwant = b.autotune()
     log(f"autotuned: persistent blocks {pblk}, far_want {fwant}")
     b.set_boundary_data(b.boundary_label())
@@ -508,7 +510,13 @@ def bench_batch(args):
                                f"particle, kappa~U[0.5,2], QBX order 10, mixed FP32/FP64 to a "
                                f"relative residual of {tol:g}; one step = batched solve + "
                                f"forces/torques of every configuration; "
-                               + (f"{int((~lane).sum())} configurations below {thr} nodes in the "
+                               + (f"every configuration in the fused engine, one graph-replayed "
+                                  f"iteration for the whole batch: {int((~lane).sum())} below "
+                                  f"{thr} nodes with the fused direct far field, {int(lane.sum())} "
+                                  f"from {thr} nodes on as trees of the FMM forest (FMM order 20 "
+                                  f"inner / 40 FP64 residuals; forces of the trees on "
+                                  f"{args.fmm_workers} worker threads)" if forest
+                                  else f"{int((~lane).sum())} configurations below {thr} nodes in the "
                                   f"fused direct engine (graph-replayed iteration), "
                                   f"{int(lane.sum())} from {thr} nodes on in the FMM lane "
                                   f"({args.fmm_workers} workers, FMM order 20 inner / 40 FP64 "

@@ -330,12 +330,19 @@ int yq_get_particles(const yq_problem* prob, double* center_xy, double* angle);
  * fused correction, batched CGS2 Arnoldi, device-side Givens), captured once as
  * a hipGraph and replayed.  A configuration's arithmetic depends only on its own
  * size, so its result is bitwise the same alone (a batch of one) or in a mix.
- * FMM lane: configurations of at least a threshold node count (params->far_mode
+ * FMM configurations: those of at least a threshold node count (params->far_mode
  * YQ_FAR_FMM: all; YQ_FAR_AUTO: 20000 nodes; YQ_FAR_DIRECT: none;
- * yq_batch_set_fmm overrides) are not engine members: each is a standalone
- * problem with the FMM far field, solved (and its forces evaluated) by worker
- * threads (default 6, largest first from a shared queue, one stream of default
- * priority each) while the engine replays its iteration graph for the rest.
+ * yq_batch_set_fmm overrides) take the quadtree FMM of section 5.  By default
+ * they stay engine members: their trees form one forest whose passes (P2M, M2M
+ * per level, M2L, L2L per level, L2P + P2P) are one launch each over every tree
+ * in the same captured iteration, the inner operator with the order-fmm_order
+ * FMM (FP32 leaf pairs and M2L) and the FP64 residuals with the order-
+ * fmm_resid_order one; each tree's arithmetic is that of the configuration
+ * solved alone.  Their forces run on worker threads (default 6, largest first,
+ * one stream of default priority each) beside the others'.  With
+ * yq_batch_set_fmm_engine(batch, 0), or when fmm_resid_order is 0 or fmm_m2l is
+ * YQ_M2L_VALU, they are standalone problems instead, solved by the worker
+ * threads while the engine replays its iteration graph for the rest.
  * The batch owns a HIP stream of default priority; every batch call is
  * synchronous (returns after its work is done) and reads its device inputs when
  * called, so the caller must have finished writing them. */
@@ -345,9 +352,14 @@ int yq_batch_create(const yq_params* params, yq_batch** out);
 void yq_batch_destroy(yq_batch* batch);
 const char* yq_batch_last_error(const yq_batch* batch);
 
-/* FMM lane threshold (nodes, >= 0) and worker count (1..8); before
+/* FMM threshold (nodes, >= 0) and worker count (1..8); before
  * yq_batch_set_configs (YQ_ESTATE after). */
 int yq_batch_set_fmm(yq_batch* batch, int64_t min_nodes, int32_t workers);
+
+/* enable != 0 (default): FMM configurations are trees of the engine's forest;
+ * 0: standalone problems solved by the worker threads.  Before
+ * yq_batch_set_configs (YQ_ESTATE after). */
+int yq_batch_set_fmm_engine(yq_batch* batch, int32_t enable);
 
 /* nparticles: host [nconf]; center_xy, angle, semi_axes: host, all configurations'
  * particles concatenated in order (layout as yq_set_particles); kappa: host [nconf].

@@ -276,9 +276,11 @@ class Batch:
     def _sync(self):
         self.torch.cuda.synchronize(self.device)
 
-    def set_fmm(self, min_nodes, workers=6):
-        """Configurations of at least min_nodes nodes take the FMM lane (before set_configs)."""
+    def set_fmm(self, min_nodes, workers=6, in_engine=True):
+        """Configurations of at least min_nodes nodes take the FMM (before set_configs):
+        as trees of the engine's forest (in_engine), else solved by worker threads."""
         self._check(self.lib.yq_batch_set_fmm(self.h, int(min_nodes), int(workers)))
+        self._check(self.lib.yq_batch_set_fmm_engine(self.h, int(bool(in_engine))))
         return self
 
     def _f64(self, *shape):

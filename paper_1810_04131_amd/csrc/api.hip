@@ -687,9 +687,10 @@ void setup_particles(yq_problem* pb, int32_t n, const double* center_xy, const d
 
   // the FMM tree is built on the host from the node positions; their copy is
   // queued now so that the QBX build below runs while the tree is built
-  const bool use_fmm = !pb->batch_member &&
-                       (pb->prm.far_mode == YQ_FAR_FMM ||
-                        (pb->prm.far_mode == YQ_FAR_AUTO && N >= kFmmAutoNodes));
+  // (a batch member takes the FMM only when its batch asks for it: its far field is
+  // then one tree of the batch engine's forest)
+  const bool use_fmm = pb->prm.far_mode == YQ_FAR_FMM ||
+                       (!pb->batch_member && pb->prm.far_mode == YQ_FAR_AUTO && N >= kFmmAutoNodes);
   if (use_fmm) {
     // the FMM objects of the previous geometry are rebuilt in place: their
     // device buffers only grow, so a new geometry frees nothing

@@ -31,6 +31,7 @@ struct ConfDev {
   int tblocks, chunks, chunk;
   int kb;         // Krylov reduction blocks
   int64_t kpoff;  // offset of its multi-dot partials
+  int fmm;        // far field from the FMM forest (part64, one chunk), not the fused sums
 };
 
 struct Member {
@@ -58,6 +59,9 @@ struct Engine {
   DevBuf<int> active, inc, jc, kc, conv;
   DevBuf<double> hb, H, cs, sn, gv, yv, scale, bnorm, rtol, res, nrm;
   DevBuf<double> V, w, r, tmp, delta, f;
+  // members with an FMM far field, as one forest per operator: the inner (FP32
+  // leaf pairs and M2L) and the FP64 residual operator (the members' order-40 FMMs)
+  FmmForest forest_in, forest_hi;
   hipGraphExec_t graph_exec[2] = {nullptr, nullptr};   // FP64, mixed iteration
   hipGraphExec_t graph_part[6] = {};                    // the same in three parts (timers on)
   // timers of the fused far-field launches: events around every launch and the

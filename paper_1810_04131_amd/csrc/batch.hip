@@ -112,6 +112,7 @@ __global__ void bpack32_kernel(const ConfDev* __restrict__ cf, const int* __rest
   const int c = node_conf[g];
   if (c < 0 || !mask[c]) return;
   const ConfDev& cd = cf[c];
+  if (cd.fmm) return;   // no FP32 source records: its far field comes from the forest
   const int64_t i = g - cd.off;
   const double sc = V[(col ? (int64_t)col[c] * T : 0) + g] * cd.f32.qc;
   const float2 r = cd.rel[i];
@@ -156,7 +157,7 @@ __global__ void bfinish_kernel(const ConfDev* __restrict__ cf, const int* __rest
   const int64_t i = g - cd.off;
   const double* sg = V + (col ? (int64_t)col[c] * T : 0) + cd.off;
   double s = 0.0;
-  if (!f32) {
+  if (!f32 || cd.fmm) {
     for (int k = 0; k < cd.chunks; ++k) s += cd.part64[(int64_t)k * N + i];
   } else {
     for (int k = 0; k < cd.chunks; ++k) s += (double)cd.part32[(int64_t)k * N + i];
@@ -364,6 +365,7 @@ void Engine::rebuild() {
   std::vector<ConfDev> h(nc);
   std::vector<int4> it;
   std::vector<int2> kb;
+  std::vector<FmmForest::Tree> tin, thi;
   int64_t kpoff = 0;
   for (int c = 0; c < nc; ++c) {
     Member& mb = members[c];
@@ -396,13 +398,24 @@ void Engine::rebuild() {
       d.kb = (int)((pb->N + KR - 1) / KR);
       d.kpoff = kpoff;
       kpoff += (int64_t)(m + 1) * d.kb;
-      for (int t = 0; t < d.tblocks; ++t)
-        for (int s = 0; s < d.chunks; ++s) it.push_back(make_int4(c, t, s, 0));
+      if (pb->fmm) {
+        // FMM member: the forests write its far field to its FP64 partial buffer
+        YQ_REQUIRE(pb->fmm_hi, YQ_EINVAL, "an FMM member of the batch engine needs fmm_resid_order > 0");
+        d.fmm = 1;
+        d.chunks = 1;
+        tin.push_back(FmmForest::Tree{pb->fmm.get(), c, mb.off, pb->partial.p, pb->tab.p});
+        thi.push_back(FmmForest::Tree{pb->fmm_hi.get(), c, mb.off, pb->partial.p, pb->tab.p});
+      } else {
+        for (int t = 0; t < d.tblocks; ++t)
+          for (int s = 0; s < d.chunks; ++s) it.push_back(make_int4(c, t, s, 0));
+      }
       for (int b = 0; b < d.kb; ++b) kb.push_back(make_int2(c, b));
     }
   }
   nitems = (int)it.size();
   nkblk = (int)kb.size();
+  forest_in.build(tin, true, stream);
+  forest_hi.build(thi, false, stream);
   conf.alloc(std::max(nc, 1));
   items.alloc(std::max(nitems, 1));
   kblk.alloc(std::max(nkblk, 1));
@@ -463,16 +476,19 @@ int Engine::grid_blocks() const {
 }
 
 // The three parts of out = A sigma (precision prec) for configurations in mask,
-// input column from V/col: 0 packs the FP32 source records (mixed only), 1 the
-// fused far-field kernel, 2 the chunk sums and near correction.
+// input column from V/col: 0 packs the FP32 source records (mixed only) and runs
+// the FMM members' forest, 1 the fused far-field kernel of the direct members, 2
+// the chunk sums (or the forest's far field) and near correction.
 void Engine::matvec_part(int part, int prec, const int* mask, const double* Vin, const int* col,
                          double* out) {
-  if (nitems == 0) return;
   unsigned long long* pc = prof_on ? prof_pairs.p + (prec == YQ_MIXED ? 1 : 0) : nullptr;
   if (part == 0) {
-    if (prec == YQ_MIXED)
+    if (prec == YQ_MIXED && nitems > 0)
       bpack32_kernel<<<nb256(T), 256, 0, stream>>>(conf.p, node_conf.p, T, mask, Vin, col);
+    // the FMM members' far field (inner operator, or the FP64 residual operator)
+    (prec == YQ_MIXED ? forest_in : forest_hi).apply(mask, Vin, col, T, stream);
   } else if (part == 1) {
+    if (nitems == 0) return;
     if (prec == YQ_MIXED)
       bfar32_kernel<<<grid_blocks(), BB, 0, stream>>>(conf.p, items.p, nitems, mask, pc);
     else

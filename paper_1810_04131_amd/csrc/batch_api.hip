@@ -29,10 +29,14 @@ struct yq_batch {
   std::string err;
   bool ready = false;
   bool have_f = false;
-  // FMM lane
+  // configurations from fmm_min_nodes on take the FMM: as trees of the engine's
+  // forest (fmm_in_engine), or as standalone problems solved by worker threads
   int64_t fmm_min_nodes = std::numeric_limits<int64_t>::max();
   int fmm_workers = 6;
-  std::vector<int> direct_idx, fmm_idx;   // configuration indices of each lane
+  bool fmm_in_engine = true;
+  std::vector<int> direct_idx;            // engine members (fused sums or forest trees)
+  std::vector<int> fmm_idx;               // worker-thread (lane) configurations
+  std::vector<int> forest_idx;            // engine members with the FMM (largest first)
   std::vector<hipStream_t> streams;       // one per worker (default priority)
   int device = 0;
   ~yq_batch() {
@@ -74,13 +78,16 @@ void sync_lane(yq_batch* b) {
   for (int c : b->fmm_idx) YQ_HIP(hipStreamSynchronize(b->probs[c]->stream));
 }
 
-// Runs job(c, pb) for every FMM-lane configuration c on the worker threads
-// (largest first, from a shared queue), each problem on its worker's stream, while
-// local() runs the fused engine's part on this thread; then waits for the workers
-// and raises the first lane failure (codes other than YQ_OK and YQ_ENOCONV).
+// Runs job(c, pb) for every configuration c of idx on the worker threads (in
+// order, from a shared queue), each problem on its worker's stream, while local()
+// runs on this thread; then waits for the workers and raises the first failure
+// (codes other than YQ_OK and YQ_ENOCONV).  restore: the problems go back to the
+// engine's stream afterwards (engine members lent to a worker; job must leave its
+// problem's stream idle, as the synchronous entry points do).
 template <class Job, class Local>
-void run_lane(yq_batch* b, Job&& job, Local&& local) {
-  const int nf = (int)b->fmm_idx.size();
+void run_workers(yq_batch* b, const std::vector<int>& idx, bool restore, Job&& job,
+                 Local&& local) {
+  const int nf = (int)idx.size();
   std::vector<int> codes(nf, YQ_OK);
   std::vector<std::string> errs(nf);
   std::atomic<int> next{0};
@@ -90,12 +97,13 @@ void run_lane(yq_batch* b, Job&& job, Local&& local) {
       workers.push_back(std::make_unique<HostThread>([&, w] {
         (void)hipSetDevice(b->device);
         for (int k = next++; k < nf; k = next++) {
-          const int c = b->fmm_idx[k];
+          const int c = idx[k];
           yq_problem* pb = b->probs[c].get();
           pb->stream = b->streams[w];   // earlier work on its stream is done (sync_lane)
           const int st = job(c, pb);
           codes[k] = st;
           if (st != YQ_OK && st != YQ_ENOCONV) errs[k] = yq_last_error(pb);
+          if (restore) pb->stream = b->eng.stream;
         }
       }));
     }
@@ -103,12 +111,13 @@ void run_lane(yq_batch* b, Job&& job, Local&& local) {
   }
   for (int k = 0; k < nf; ++k)
     YQ_REQUIRE(codes[k] == YQ_OK || codes[k] == YQ_ENOCONV, codes[k],
-               "configuration " + std::to_string(b->fmm_idx[k]) + ": " + errs[k]);
+               "configuration " + std::to_string(idx[k]) + ": " + errs[k]);
 }
 
 void rebuild_plans(yq_batch* b) {
   for (int c : b->direct_idx) {
     yq_problem* pb = b->probs[c].get();
+    if (pb->fmm) continue;   // a forest tree: no fused far-field plan
     pb->far_want = b->far_want;
     pb->fp = far_plan(pb->N, pb->N, 256, b->far_want);
     pb->partial.alloc((size_t)pb->fp.chunks * pb->N);
@@ -166,15 +175,20 @@ int yq_batch_set_configs(yq_batch* b, int32_t nconf, const int32_t* np, const do
     b->eng.members.clear();
     b->direct_idx.clear();
     b->fmm_idx.clear();
+    b->forest_idx.clear();
     b->offsets.assign(nconf + 1, 0);
     b->poffsets.assign(nconf + 1, 0);
     int64_t pofs = 0;
     for (int c = 0; c < nconf; ++c) {
       YQ_REQUIRE(np[c] >= 1, YQ_EINVAL, "configuration " + std::to_string(c) + " has no particles");
       const int64_t Nc = (int64_t)np[c] * b->prm.panels_per_particle * Q;
-      const bool lane = Nc >= b->fmm_min_nodes;
+      const bool big = Nc >= b->fmm_min_nodes;
+      // a forest tree needs the MFMA translations and the FP64 residual FMM
+      const bool tree = big && b->fmm_in_engine && b->prm.fmm_resid_order > 0 &&
+                        b->prm.fmm_m2l != YQ_M2L_VALU;
+      const bool lane = big && !tree;
       yq_params p = b->prm;
-      if (lane) p.far_mode = YQ_FAR_FMM;
+      if (big) p.far_mode = YQ_FAR_FMM;
       yq_problem* pb = nullptr;
       int st = yq_create(&p, &pb);
       YQ_REQUIRE(st == YQ_OK, st, "yq_create failed");
@@ -186,6 +200,7 @@ int yq_batch_set_configs(yq_batch* b, int32_t nconf, const int32_t* np, const do
         pb->batch_member = true;
         pb->stream = b->eng.stream;
         b->direct_idx.push_back(c);
+        if (tree) b->forest_idx.push_back(c);
       }
       st = yq_set_particles(pb, np[c], center_xy + 2 * pofs, angle + pofs, semi_axes + 2 * pofs,
                             kappa[c]);
@@ -201,12 +216,15 @@ int yq_batch_set_configs(yq_batch* b, int32_t nconf, const int32_t* np, const do
     b->eng.T = b->offsets[nconf];
     for (int c : b->direct_idx) b->eng.members.push_back(Member{b->probs[c].get(), b->offsets[c]});
     if (!b->direct_idx.empty()) b->eng.rebuild();
-    // FMM lane: largest first, one stream per worker
-    std::sort(b->fmm_idx.begin(), b->fmm_idx.end(), [&](int x, int y) {
+    // worker threads take the largest configurations first; one stream per worker
+    auto largest_first = [&](int x, int y) {
       const int64_t nx = b->offsets[x + 1] - b->offsets[x], ny = b->offsets[y + 1] - b->offsets[y];
       return nx != ny ? nx > ny : x < y;
-    });
-    const int nw = std::min<int>(b->fmm_workers, (int)b->fmm_idx.size());
+    };
+    std::sort(b->fmm_idx.begin(), b->fmm_idx.end(), largest_first);
+    std::sort(b->forest_idx.begin(), b->forest_idx.end(), largest_first);
+    const int nw = std::min<int>(b->fmm_workers,
+                                 (int)std::max(b->fmm_idx.size(), b->forest_idx.size()));
     while ((int)b->streams.size() < nw) {
       hipStream_t s = nullptr;
       YQ_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
@@ -286,8 +304,8 @@ int yq_batch_solve(yq_batch* b, double* sigma, yq_solve_info* info) {
     // the fused iteration's graphs are captured before any worker starts, so no
     // capture overlaps the workers' allocations
     if (!b->direct_idx.empty()) b->eng.ensure_graphs();
-    run_lane(
-        b,
+    run_workers(
+        b, b->fmm_idx, false,
         [&](int c, yq_problem* pb) {
           return yq_solve(pb, nullptr, sigma + b->offsets[c], &all[c]);
         },
@@ -319,14 +337,22 @@ int yq_batch_forces(yq_batch* b, const double* sigma, double gamma, double* forc
       return yq_forces(pb, sigma + b->offsets[c], gamma, force + 2 * b->poffsets[c],
                        torque + b->poffsets[c], &en[c]);
     };
-    // the FMM lane's gradient passes on the worker threads, the direct members' here
-    run_lane(b, one, [&] {
+    // the FMM configurations' gradient passes on the worker threads (the lane's,
+    // or the forest trees' lent from the engine's stream), the others' here
+    YQ_HIP(hipStreamSynchronize(b->eng.stream));
+    std::vector<char> on_worker(b->probs.size(), 0);
+    for (int c : b->forest_idx) on_worker[c] = 1;
+    // (a batch's FMM configurations are all lane problems or all forest trees)
+    const std::vector<int>& widx = b->fmm_idx.empty() ? b->forest_idx : b->fmm_idx;
+    run_workers(b, widx, b->fmm_idx.empty(), one, [&] {
       for (int c : b->direct_idx) {
+        if (b->fmm_idx.empty() && on_worker[c]) continue;
         yq_problem* pb = b->probs[c].get();
         const int st = one(c, pb);
         YQ_REQUIRE(st == YQ_OK, st, yq_last_error(pb));
       }
     });
+
     if (energy)
       for (size_t c = 0; c < en.size(); ++c) energy[c] = en[c];
   });
@@ -340,6 +366,14 @@ int yq_batch_set_fmm(yq_batch* b, int64_t min_nodes, int32_t workers) {
     YQ_REQUIRE(!b->ready, YQ_ESTATE, "the FMM lane is set before yq_batch_set_configs");
     b->fmm_min_nodes = min_nodes;
     b->fmm_workers = workers;
+  });
+}
+
+int yq_batch_set_fmm_engine(yq_batch* b, int32_t enable) {
+  return bguard(b, [&] {
+    YQ_REQUIRE(b, YQ_EINVAL, "null batch");
+    YQ_REQUIRE(!b->ready, YQ_ESTATE, "the FMM mode is set before yq_batch_set_configs");
+    b->fmm_in_engine = enable != 0;
   });
 }
 

@@ -21,7 +21,16 @@ struct FmmLevel {
   double2* L = nullptr;
 };
 
-struct M2LLevels;   // per-level views of the M2L kernels (fmm.hip)
+constexpr int DMAX = 14;   // deepest quadtree level
+
+// Per-level views of one tree for the M2L kernels.
+struct M2LLevels {
+  const int* ild[DMAX + 1];
+  const double2* M[DMAX + 1];
+  double2* L[DMAX + 1];
+  int nbox[DMAX + 1];
+  int64_t off[DMAX + 2];     // first box of each level in the packed multipoles (off[depth + 1] = total)
+};
 
 struct Fmm {
   int p = 20;
@@ -96,6 +105,67 @@ struct Fmm {
   void apply_grad(const double* sigma, double* gpart, const double* tab, hipStream_t s);
   void apply(const double* sigma, double* partial, bool p2p_fp32, const double* tab,
              hipStream_t s, const int* stop = nullptr);
+};
+
+// One tree of an FMM forest as the forest kernels see it (device copy): the
+// member's own sorted nodes, leaves, lists, expansions and tables, the batch
+// configuration it belongs to (mask, Krylov column) and where its density and its
+// far field live.
+struct FmmDev {
+  int cfg;                 // configuration index in the batch engine
+  int depth, nleaf;
+  int64_t N, off;          // nodes; offset of the configuration in the batch vectors
+  double kappa;
+  const int* perm;
+  const double *xs, *ys, *wnxs, *wnys;
+  double *qx, *qy;
+  const int *leaf_start, *leaf_cnt, *leaf_gid, *nbp, *nbi;
+  const double *leaf_cx, *leaf_cy;
+  double2 *Mall, *Lall;
+  M2LLevels lv;
+  const int* ch[DMAX + 1];
+  const double* gmat;      // M2M / L2L matrices
+  const void* amat;        // M2L matrices (FP64, or the scaled FP32 copy)
+  void* mpk;               // packed multipoles (FP64 or FP32)
+  const double* msc;
+  const int2* m2l_tiles;
+  const double* tab;
+  double* out;             // far field of the member's nodes, node order (2 pi / kappa^2 scaling)
+};
+
+// Many quadtrees (one per batch configuration, all of one expansion order) whose
+// FMM passes run as one launch per pass over every tree: gather, P2M, M2M per
+// level, multipole packing, M2L (all levels), L2L per level, L2P + P2P.  Each
+// tree's arithmetic is that of Fmm::apply on it alone; a block whose
+// configuration's mask entry is 0 does nothing, so the launch sequence is fixed
+// and can be captured in a graph.
+struct FmmForest {
+  int p = 0, R16 = 0, depth = 0;
+  bool f32 = false;              // FP32 leaf pairs (the inner operator)
+  int nmem = 0;
+  DevBuf<FmmDev> dev;
+  // work items (member, index within the member's launch of that pass)
+  DevBuf<int2> it_gather, it_p2m, it_pack, it_m2l, it_leaf2, it_leaf4;
+  std::vector<DevBuf<int2>> it_tree;   // per parent level l: M2M into / L2L out of level l
+  int n_gather = 0, n_p2m = 0, n_pack = 0, n_m2l = 0, n_leaf2 = 0, n_leaf4 = 0;
+  std::vector<int> n_tree;
+  bool m2l32 = false;            // FP32 M2L (the trees' want_m2l32, inner operator only)
+  // A member: its built FMM, its batch configuration, the offset of that
+  // configuration in the batch vectors, the far-field output (FP64, node order,
+  // the far-field kernels' 2 pi / kappa^2 scaling) and its FP64 Bessel table.
+  struct Tree {
+    Fmm* fmm;
+    int cfg;
+    int64_t off;
+    double* out;
+    const double* tab;
+  };
+  // p2p32: FP32 leaf pairs (and FP32 M2L where the trees were set up for it), as
+  // the inner operator's Fmm::apply; else FP64 throughout.  All trees must share
+  // one order and use the MFMA translations.  Synchronises s.
+  void build(const std::vector<Tree>& trees, bool p2p32, hipStream_t s);
+  // far field of every masked member for the density V + col[cfg] * T + off
+  void apply(const int* mask, const double* V, const int* col, int64_t T, hipStream_t s) const;
 };
 
 }  // namespace yq

@@ -183,14 +183,23 @@ __global__ __launch_bounds__(TAB_BS) void tab_s_kernel(int p, double W, double k
 
 // ---- per-application kernels -----------------------------------------------------------------
 
+// Sorted node k's source strength w nu sigma (the kernels' q).
+__device__ __forceinline__ void gather_one(int64_t k, const int* __restrict__ perm,
+                                           const double* __restrict__ sigma,
+                                           const double* __restrict__ wnxs,
+                                           const double* __restrict__ wnys, double* __restrict__ qx,
+                                           double* __restrict__ qy) {
+  const double s = sigma[perm[k]];
+  qx[k] = wnxs[k] * s;
+  qy[k] = wnys[k] * s;
+}
+
 __global__ void gather_kernel(int64_t N, const int* __restrict__ perm, const double* __restrict__ sigma,
                               const double* __restrict__ wnxs, const double* __restrict__ wnys,
                               double* __restrict__ qx, double* __restrict__ qy) {
   const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (k >= N) return;
-  const double s = sigma[perm[k]];
-  qx[k] = wnxs[k] * s;
-  qy[k] = wnys[k] * s;
+  gather_one(k, perm, sigma, wnxs, wnys, qx, qy);
 }
 
 constexpr int FB = 64;
@@ -199,22 +208,18 @@ constexpr int FB = 64;
 // node at a time, rolls I_{n-1}, I_n, I_{n+1} and e^{i(n +- 1) phi} along n, and
 // the wave sums each coefficient; lane n keeps M_n.  Leaf b's coefficients go to
 // box gid[b] of M.
-__global__ __launch_bounds__(64) void p2m_kernel(int p, int use_col, double kappa,
-                                                 const int* __restrict__ ls,
-                                                 const int* __restrict__ lc,
-                                                 const int* __restrict__ gid,
-                                                 const double* __restrict__ ccx,
-                                                 const double* __restrict__ ccy,
-                                                 const double* __restrict__ xs,
-                                                 const double* __restrict__ ys,
-                                                 const double* __restrict__ qx,
-                                                 const double* __restrict__ qy,
-                                                 double2* __restrict__ M,
-                                                 const int* __restrict__ stop) {
-  if (stop && *stop) return;   // a GMRES step queued after the stop
-  extern __shared__ double itab[];   // [(p + 2) * 64]: scaled I_n, one column per lane
+// itab: [(p + 2) * 64] doubles of LDS (scaled I_n, one column per lane) when use_col.
+__device__ __forceinline__ void p2m_leaf(int b, int p, int use_col, double kappa,
+                                         const int* __restrict__ ls, const int* __restrict__ lc,
+                                         const int* __restrict__ gid,
+                                         const double* __restrict__ ccx,
+                                         const double* __restrict__ ccy,
+                                         const double* __restrict__ xs,
+                                         const double* __restrict__ ys,
+                                         const double* __restrict__ qx,
+                                         const double* __restrict__ qy, double2* __restrict__ M,
+                                         double* itab) {
   const int lane = threadIdx.x;
-  const int b = blockIdx.x;
   const int s0 = ls[b], cnt = lc[b];
   const double cx = ccx[b], cy = ccy[b];
   double* col = itab + lane;
@@ -262,6 +267,23 @@ __global__ __launch_bounds__(64) void p2m_kernel(int p, int use_col, double kapp
     const double sc = kappa / (4.0 * PI);
     M[(int64_t)gid[b] * (p + 1) + lane] = make_double2(mine.x * sc, mine.y * sc);
   }
+}
+
+__global__ __launch_bounds__(64) void p2m_kernel(int p, int use_col, double kappa,
+                                                 const int* __restrict__ ls,
+                                                 const int* __restrict__ lc,
+                                                 const int* __restrict__ gid,
+                                                 const double* __restrict__ ccx,
+                                                 const double* __restrict__ ccy,
+                                                 const double* __restrict__ xs,
+                                                 const double* __restrict__ ys,
+                                                 const double* __restrict__ qx,
+                                                 const double* __restrict__ qy,
+                                                 double2* __restrict__ M,
+                                                 const int* __restrict__ stop) {
+  if (stop && *stop) return;   // a GMRES step queued after the stop
+  extern __shared__ double itab[];
+  p2m_leaf(blockIdx.x, p, use_col, kappa, ls, lc, gid, ccx, ccy, xs, ys, qx, qy, M, itab);
 }
 
 // M2M: parent level lp from children at level lp + 1 (table level lp + 1).
@@ -320,7 +342,6 @@ __global__ void m2l_kernel(int p, int nbox, const int* __restrict__ ilp, const i
 // accuracy).  All levels go in one launch: their M2L terms are independent.
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
-constexpr int DMAX = 14;   // deepest quadtree level
 
 // Translation matrices in the operand order of the 16x16x4 product: lane =
 // i + 16 kk holds A[16 rt + i][4 ks + kk].  Row order (packed = 0, the M2M and
@@ -432,14 +453,6 @@ __device__ __forceinline__ int far_offset(int i) {
   return i + 9;                                           // ox = 2, 3
 }
 
-struct M2LLevels {
-  const int* ild[DMAX + 1];
-  const double2* M[DMAX + 1];
-  double2* L[DMAX + 1];
-  int nbox[DMAX + 1];
-  int64_t off[DMAX + 2];     // first box of each level in the packed multipoles (off[depth + 1] = total)
-};
-
 // Scaled FP32 copy of the M2L matrices (the lane order of trans_amat_kernel with
 // packed = 1): amat32 = A_mn / (s_m s_n), s = msc of the matrix's level.
 __global__ void trans_amat32_kernel(int nlev, int p, int R, const double* __restrict__ amat,
@@ -467,11 +480,10 @@ __global__ void trans_amat32_kernel(int nlev, int p, int R, const double* __rest
 // with kk = lane / 16 loads its KS operands with a few wide loads.  T = float
 // scales by s_n of the box's level (msc) for the FP32 products.
 template <typename T>
-__global__ void m2l_pack_kernel(int p, int R, int64_t g0, int64_t g1, M2LLevels lv,
-                                const double2* __restrict__ Mall, const double* __restrict__ msc,
-                                T* __restrict__ Mp) {
-  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (t >= (g1 - g0) * R) return;
+__device__ __forceinline__ void m2l_pack_one(int64_t t, int p, int R, int64_t g0,
+                                             const M2LLevels& lv,
+                                             const double2* __restrict__ Mall,
+                                             const double* __restrict__ msc, T* __restrict__ Mp) {
   const int64_t g = g0 + t / R;
   const int e = (int)(t % R);
   const int KS = R / 4, kk = e / KS, ks = e % KS;
@@ -491,6 +503,15 @@ __global__ void m2l_pack_kernel(int p, int R, int64_t g0, int64_t g1, M2LLevels 
   Mp[g * R + e] = (T)v;
 }
 
+template <typename T>
+__global__ void m2l_pack_kernel(int p, int R, int64_t g0, int64_t g1, M2LLevels lv,
+                                const double2* __restrict__ Mall, const double* __restrict__ msc,
+                                T* __restrict__ Mp) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= (g1 - g0) * R) return;
+  m2l_pack_one<T>(t, p, R, g0, lv, Mall, msc, Mp);
+}
+
 // M2L on the matrix cores: L_m(t) = sum over the 40 far offsets o of A_o M(source at
 // o), for one 16-box tile of one level per block (4 waves; wave w takes offsets w,
 // w + 4, ...).  A wave loads each offset's 16 source vectors once (zero where a
@@ -501,19 +522,15 @@ __global__ void m2l_pack_kernel(int p, int R, int64_t g0, int64_t g1, M2LLevels 
 // FP32 range, and L_m = (sum) s_m.  The four waves' tiles are summed in FP64 in a
 // fixed order.  Result layouts: FP64, lane l holds column l % 16, register j row
 // 4 j + l / 16; FP32, column l % 16, register j row 4 (l / 16) + j.
+// One tile tl = (level, first box); red: 3 RT 64 dbl4 of LDS.
 template <typename T, int RT>
-__global__ __launch_bounds__(256) void m2l_mfma_kernel(int p, const int2* __restrict__ tiles,
-                                                       M2LLevels lv, const T* __restrict__ amat,
-                                                       const T* __restrict__ Mp,
-                                                       const double* __restrict__ msc,
-                                                       const int* __restrict__ stop) {
-  if (stop && *stop) return;
+__device__ __forceinline__ void m2l_tile(int2 tl, int p, const M2LLevels& lv,
+                                         const T* __restrict__ amat, const T* __restrict__ Mp,
+                                         const double* __restrict__ msc, dbl4* red) {
   constexpr int R = RT * 16, KS = R / 4, NI = 10;
   constexpr bool F32 = sizeof(T) == 4;
   using acc_t = typename std::conditional<F32, f32x4, dbl4>::type;
-  __shared__ dbl4 red[3 * RT * 64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int2 tl = tiles[blockIdx.x];       // (level, first box)
   const int l = tl.x, nbox = lv.nbox[l];
   const int* __restrict__ ild = lv.ild[l];
   const int P1 = p + 1;
@@ -568,22 +585,34 @@ __global__ __launch_bounds__(256) void m2l_mfma_kernel(int p, const int2* __rest
   }
 }
 
+template <typename T, int RT>
+__global__ __launch_bounds__(256) void m2l_mfma_kernel(int p, const int2* __restrict__ tiles,
+                                                       M2LLevels lv, const T* __restrict__ amat,
+                                                       const T* __restrict__ Mp,
+                                                       const double* __restrict__ msc,
+                                                       const int* __restrict__ stop) {
+  if (stop && *stop) return;
+  __shared__ dbl4 red[3 * RT * 64];
+  m2l_tile<T, RT>(tiles[blockIdx.x], p, lv, amat, Mp, msc, red);
+}
+
 // M2M (GATHER: parent tiles at level l, y = sum over the 4 children of A_pos x_child)
 // and L2L (scatter: parent tiles, child_pos += A_pos x_parent), one level per
 // launch, one block (4 waves, wave = child position) per (16-box tile, row
 // tile); A points at the child level's 4 matrices, ch is the children table.
+// Block bx of the level's launch ((16-box tile, row tile) = (bx / RT, bx % RT)); red:
+// 3 x 64 dbl4 of LDS.
 template <int RT, bool GATHER>
-__global__ __launch_bounds__(256) void tree_mfma_kernel(int p, int nbox, const int* __restrict__ ch,
-                                                        const double2* __restrict__ X,
-                                                        const double* __restrict__ amat,
-                                                        double2* __restrict__ Y) {
+__device__ __forceinline__ void tree_tile(int bx, int p, int nbox, const int* __restrict__ ch,
+                                          const double2* __restrict__ X,
+                                          const double* __restrict__ amat,
+                                          double2* __restrict__ Y, dbl4* red) {
   constexpr int R = RT * 16, KS = R / 4;
-  __shared__ dbl4 red[3 * 64];
   const int lane = threadIdx.x & 63, pos = threadIdx.x >> 6;
-  const int rt = blockIdx.x % RT;
+  const int rt = bx % RT;
   const int P1 = p + 1;
   const int col = lane & 15, kk = lane >> 4;
-  const int tb = (blockIdx.x / RT) * 16 + col;
+  const int tb = (bx / RT) * 16 + col;
   const double* A = amat + (int64_t)pos * R * R + (int64_t)rt * KS * 64 + lane;
   const int c = tb < nbox ? ch[4 * (int64_t)tb + pos] : -1;
   TileOps<KS> op;
@@ -601,6 +630,15 @@ __global__ __launch_bounds__(256) void tree_mfma_kernel(int p, int nbox, const i
     const dbl4 acc = tile_mfma<KS>(op, dbl4{0.0, 0.0, 0.0, 0.0});
     if (c >= 0) tile_store<true>(Y + (int64_t)c * P1, rt, kk, P1, acc);
   }
+}
+
+template <int RT, bool GATHER>
+__global__ __launch_bounds__(256) void tree_mfma_kernel(int p, int nbox, const int* __restrict__ ch,
+                                                        const double2* __restrict__ X,
+                                                        const double* __restrict__ amat,
+                                                        double2* __restrict__ Y) {
+  __shared__ dbl4 red[3 * 64];
+  tree_tile<RT, GATHER>(blockIdx.x, p, nbox, ch, X, amat, Y, red);
 }
 
 // L2L: child level lc from parents (table level lc), accumulated.
@@ -642,26 +680,23 @@ __device__ __forceinline__ void wave_sync() {
 // One block per leaf: local expansion at the leaf's targets plus the direct
 // interactions with the leaves of its P2P list; writes partial[node] in the
 // far-field kernels' scaling (far field * 2 pi / kappa^2).
+// Leaf b; sh: the kernel's dynamic LDS (leaf_lds_bytes).
 template <bool F32, int NW>
-__global__ __launch_bounds__(FB * NW) void l2p_p2p_kernel(int p, double kappa, int use_local, int use_col,
-                                                          const int* __restrict__ ls,
-                                                          const int* __restrict__ lc,
-                                                          const int* __restrict__ gid,
-                                                          const int* __restrict__ nbp,
-                                                          const int* __restrict__ nbi,
-                                                          const double* __restrict__ ccx,
-                                                          const double* __restrict__ ccy,
-                                                          const double2* __restrict__ L,
-                                                          const double* __restrict__ xs,
-                                                          const double* __restrict__ ys,
-                                                          const double* __restrict__ qx,
-                                                          const double* __restrict__ qy,
-                                                          const int* __restrict__ perm,
-                                                          const double* __restrict__ tab,
-                                                          double* __restrict__ partial,
-                                                          const int* __restrict__ stop) {
-  if (stop && *stop) return;
-  extern __shared__ double sh[];
+__device__ __forceinline__ void leaf_pass(int b, int p, double kappa, int use_local, int use_col,
+                                          const int* __restrict__ ls, const int* __restrict__ lc,
+                                          const int* __restrict__ gid,
+                                          const int* __restrict__ nbp,
+                                          const int* __restrict__ nbi,
+                                          const double* __restrict__ ccx,
+                                          const double* __restrict__ ccy,
+                                          const double2* __restrict__ L,
+                                          const double* __restrict__ xs,
+                                          const double* __restrict__ ys,
+                                          const double* __restrict__ qx,
+                                          const double* __restrict__ qy,
+                                          const int* __restrict__ perm,
+                                          const double* __restrict__ tab,
+                                          double* __restrict__ partial, double* sh) {
   const int lane = threadIdx.x % FB, w = threadIdx.x / FB;
   double2* sbase = reinterpret_cast<double2*>(sh);
   double2* sxy = sbase + w * FB;                                        // [NW][FB]
@@ -670,7 +705,6 @@ __global__ __launch_bounds__(FB * NW) void l2p_p2p_kernel(int p, double kappa, i
   double* red = reinterpret_cast<double*>(reinterpret_cast<float2*>(sbase + 2 * NW * FB) +
                                           NW * FB);                     // [NW][FB] wave sums
   double* col = red + NW * FB + lane;   // [(p + 1) * 64] scaled I_n, wave 0
-  const int b = blockIdx.x;
   const int s0 = ls[b], cnt = lc[b];
   const double kap2 = kappa * kappa;
   const double cx = ccx[b], cy = ccy[b];
@@ -728,6 +762,30 @@ __global__ __launch_bounds__(FB * NW) void l2p_p2p_kernel(int p, double kappa, i
     }
     __syncthreads();   // red is rewritten by the next group of targets
   }
+}
+
+template <bool F32, int NW>
+__global__ __launch_bounds__(FB * NW) void l2p_p2p_kernel(int p, double kappa, int use_local, int use_col,
+                                                          const int* __restrict__ ls,
+                                                          const int* __restrict__ lc,
+                                                          const int* __restrict__ gid,
+                                                          const int* __restrict__ nbp,
+                                                          const int* __restrict__ nbi,
+                                                          const double* __restrict__ ccx,
+                                                          const double* __restrict__ ccy,
+                                                          const double2* __restrict__ L,
+                                                          const double* __restrict__ xs,
+                                                          const double* __restrict__ ys,
+                                                          const double* __restrict__ qx,
+                                                          const double* __restrict__ qy,
+                                                          const int* __restrict__ perm,
+                                                          const double* __restrict__ tab,
+                                                          double* __restrict__ partial,
+                                                          const int* __restrict__ stop) {
+  if (stop && *stop) return;
+  extern __shared__ double sh[];
+  leaf_pass<F32, NW>(blockIdx.x, p, kappa, use_local, use_col, ls, lc, gid, nbp, nbi, ccx, ccy, L,
+                     xs, ys, qx, qy, perm, tab, partial, sh);
 }
 
 // Gradient counterpart of l2p_p2p_kernel (FP64): the direct gradient from the
@@ -1384,6 +1442,266 @@ void Fmm::apply_grad(const double* sigma, double* gpart, const double* tab, hipS
                                                   leaf_gid.p, nbp.p, nbi.p, leaf_cx.p, leaf_cy.p,
                                                   Lall.p, xs.p, ys.p, qx.p, qy.p, perm.p, N, tab,
                                                   gpart);
+  YQ_HIP(hipGetLastError());
+}
+
+// ---- forest: one launch per pass over many trees ------------------------------------------
+//
+// Every block reads its work item (member, index), skips the member when its batch
+// configuration is masked off, and runs the same body as the single-tree kernel's
+// block of that index, so each tree's sums are those of Fmm::apply.
+
+__global__ void forest_gather_kernel(const FmmDev* __restrict__ fd, const int2* __restrict__ items,
+                                     const int* __restrict__ mask, const double* __restrict__ V,
+                                     const int* __restrict__ col, int64_t T) {
+  const int2 it = items[blockIdx.x];
+  const FmmDev& d = fd[it.x];
+  if (!mask[d.cfg]) return;
+  const int64_t k = (int64_t)it.y * 256 + threadIdx.x;
+  if (k >= d.N) return;
+  const double* sigma = V + (col ? (int64_t)col[d.cfg] * T : 0) + d.off;
+  gather_one(k, d.perm, sigma, d.wnxs, d.wnys, d.qx, d.qy);
+}
+
+__global__ __launch_bounds__(64) void forest_p2m_kernel(const FmmDev* __restrict__ fd,
+                                                        const int2* __restrict__ items,
+                                                        const int* __restrict__ mask, int p,
+                                                        int use_col) {
+  extern __shared__ double itab[];
+  const int2 it = items[blockIdx.x];
+  const FmmDev& d = fd[it.x];
+  if (!mask[d.cfg]) return;
+  p2m_leaf(it.y, p, use_col, d.kappa, d.leaf_start, d.leaf_cnt, d.leaf_gid, d.leaf_cx, d.leaf_cy,
+           d.xs, d.ys, d.qx, d.qy, d.Mall, itab);
+}
+
+// M2M into parent level l (GATHER) or L2L out of it, for every member deep enough.
+template <int RT, bool GATHER>
+__global__ __launch_bounds__(256) void forest_tree_kernel(const FmmDev* __restrict__ fd,
+                                                          const int2* __restrict__ items,
+                                                          const int* __restrict__ mask, int p,
+                                                          int l) {
+  __shared__ dbl4 red[3 * 64];
+  const int2 it = items[blockIdx.x];
+  const FmmDev& d = fd[it.x];
+  if (!mask[d.cfg]) return;
+  constexpr int R = RT * 16;
+  const double* A = d.gmat + (size_t)(l + 1) * 4 * R * R;
+  const double2* X = GATHER ? d.lv.M[l + 1] : d.lv.L[l];
+  double2* Y = GATHER ? const_cast<double2*>(d.lv.M[l]) : d.lv.L[l + 1];
+  tree_tile<RT, GATHER>(it.y, p, d.lv.nbox[l], d.ch[l], X, A, Y, red);
+}
+
+template <typename T>
+__global__ void forest_pack_kernel(const FmmDev* __restrict__ fd, const int2* __restrict__ items,
+                                   const int* __restrict__ mask, int p, int R) {
+  const int2 it = items[blockIdx.x];
+  const FmmDev& d = fd[it.x];
+  if (!mask[d.cfg]) return;
+  const int64_t g0 = d.lv.off[2], g1 = d.lv.off[d.depth + 1];
+  const int64_t t = (int64_t)it.y * 256 + threadIdx.x;
+  if (t >= (g1 - g0) * R) return;
+  m2l_pack_one<T>(t, p, R, g0, d.lv, d.Mall, d.msc, static_cast<T*>(d.mpk));
+}
+
+template <typename T, int RT>
+__global__ __launch_bounds__(256) void forest_m2l_kernel(const FmmDev* __restrict__ fd,
+                                                         const int2* __restrict__ items,
+                                                         const int* __restrict__ mask, int p) {
+  __shared__ dbl4 red[3 * RT * 64];
+  const int2 it = items[blockIdx.x];
+  const FmmDev& d = fd[it.x];
+  if (!mask[d.cfg]) return;
+  m2l_tile<T, RT>(d.m2l_tiles[it.y], p, d.lv, static_cast<const T*>(d.amat),
+                  static_cast<const T*>(d.mpk), d.msc, red);
+}
+
+template <bool F32, int NW>
+__global__ __launch_bounds__(FB * NW) void forest_leaf_kernel(const FmmDev* __restrict__ fd,
+                                                              const int2* __restrict__ items,
+                                                              const int* __restrict__ mask, int p,
+                                                              int use_col) {
+  extern __shared__ double sh[];
+  const int2 it = items[blockIdx.x];
+  const FmmDev& d = fd[it.x];
+  if (!mask[d.cfg]) return;
+  leaf_pass<F32, NW>(it.y, p, d.kappa, 1, use_col, d.leaf_start, d.leaf_cnt, d.leaf_gid, d.nbp,
+                     d.nbi, d.leaf_cx, d.leaf_cy, d.Lall, d.xs, d.ys, d.qx, d.qy, d.perm, d.tab,
+                     d.out, sh);
+}
+
+namespace {
+
+size_t leaf_lds_bytes(int nw, int p, int use_col) {
+  return (size_t)nw * FB * (2 * sizeof(double2) + sizeof(float2) + sizeof(double)) +
+         (use_col ? (size_t)(p + 1) * 64 * sizeof(double) : 0);
+}
+
+template <class V>
+void upload_items(DevBuf<V>& d, const std::vector<V>& h, hipStream_t s) {
+  d.fit(std::max<size_t>(h.size(), 1));
+  if (!h.empty())
+    YQ_HIP(hipMemcpyAsync(d.p, h.data(), h.size() * sizeof(V), hipMemcpyHostToDevice, s));
+}
+
+}  // namespace
+
+void FmmForest::build(const std::vector<Tree>& trees, bool p2p32, hipStream_t s) {
+  nmem = (int)trees.size();
+  f32 = p2p32;
+  depth = 0;
+  n_gather = n_p2m = n_pack = n_m2l = n_leaf2 = n_leaf4 = 0;
+  if (nmem == 0) return;
+  p = trees[0].fmm->p;
+  R16 = trees[0].fmm->R16;
+  m2l32 = p2p32 && trees[0].fmm->want_m2l32;
+  std::vector<FmmDev> h(nmem);
+  std::vector<int2> g, pm, pk, ml, l2, l4;
+  std::vector<std::vector<int2>> tr(DMAX + 1);
+  for (int m = 0; m < nmem; ++m) {
+    Fmm& f = *trees[m].fmm;
+    YQ_REQUIRE(f.built && f.p == p && f.R16 == R16 && f.use_mfma &&
+                   (p2p32 ? f.want_m2l32 == trees[0].fmm->want_m2l32 : true),
+               YQ_EINVAL, "FMM forest: trees of different orders or translation modes");
+    FmmDev& d = h[m];
+    std::memset(&d, 0, sizeof(d));
+    d.cfg = trees[m].cfg;
+    d.depth = f.depth;
+    d.nleaf = f.nleaf;
+    d.N = f.N;
+    d.off = trees[m].off;
+    d.kappa = f.kappa;
+    d.perm = f.perm.p;
+    d.xs = f.xs.p;
+    d.ys = f.ys.p;
+    d.wnxs = f.wnxs.p;
+    d.wnys = f.wnys.p;
+    d.qx = f.qx.p;
+    d.qy = f.qy.p;
+    d.leaf_start = f.leaf_start.p;
+    d.leaf_cnt = f.leaf_cnt.p;
+    d.leaf_gid = f.leaf_gid.p;
+    d.nbp = f.nbp.p;
+    d.nbi = f.nbi.p;
+    d.leaf_cx = f.leaf_cx.p;
+    d.leaf_cy = f.leaf_cy.p;
+    d.Mall = f.Mall.p;
+    d.Lall = f.Lall.p;
+    d.lv = f.m2l_levels();
+    for (int l = 0; l <= f.depth; ++l) d.ch[l] = f.lv[l].ch.p;
+    d.gmat = f.gmat.p;
+    d.msc = f.msc.p;
+    d.m2l_tiles = f.m2l_tiles.p;
+    d.tab = trees[m].tab;
+    d.out = trees[m].out;
+    if (m2l32) {
+      f.mpk32.fit((size_t)f.nbox_total * R16);
+      d.amat = f.amat32.p;
+      d.mpk = f.mpk32.p;
+    } else {
+      f.mpk64.fit((size_t)f.nbox_total * R16);
+      d.amat = f.amat.p;
+      d.mpk = f.mpk64.p;
+    }
+    depth = std::max(depth, f.depth);
+    for (int64_t b = 0; b < (f.N + 255) / 256; ++b) g.push_back(make_int2(m, (int)b));
+    for (int b = 0; b < f.nleaf; ++b) pm.push_back(make_int2(m, b));
+    const int RT = R16 / 16;
+    for (int l = 2; l < f.depth; ++l) {
+      const int nb = f.lv[l].nbox;
+      for (int bx = 0; bx < ((nb + 15) / 16) * RT; ++bx) tr[l].push_back(make_int2(m, bx));
+    }
+    if (f.n_m2l_tiles > 0 && f.depth >= 2) {
+      const int64_t ne = (f.nbox_total - f.lv[2].off) * R16;
+      for (int64_t b = 0; b < (ne + 255) / 256; ++b) pk.push_back(make_int2(m, (int)b));
+      for (int t = 0; t < f.n_m2l_tiles; ++t) ml.push_back(make_int2(m, t));
+    }
+    auto& lst = f.nleaf >= kLeavesFor2 ? l2 : l4;
+    for (int b = 0; b < f.nleaf; ++b) lst.push_back(make_int2(m, b));
+  }
+  dev.fit(nmem);
+  YQ_HIP(hipMemcpyAsync(dev.p, h.data(), nmem * sizeof(FmmDev), hipMemcpyHostToDevice, s));
+  upload_items(it_gather, g, s);
+  upload_items(it_p2m, pm, s);
+  upload_items(it_pack, pk, s);
+  upload_items(it_m2l, ml, s);
+  upload_items(it_leaf2, l2, s);
+  upload_items(it_leaf4, l4, s);
+  n_gather = (int)g.size();
+  n_p2m = (int)pm.size();
+  n_pack = (int)pk.size();
+  n_m2l = (int)ml.size();
+  n_leaf2 = (int)l2.size();
+  n_leaf4 = (int)l4.size();
+  it_tree.resize(DMAX + 1);
+  n_tree.assign(DMAX + 1, 0);
+  for (int l = 0; l <= DMAX; ++l) {
+    upload_items(it_tree[l], tr[l], s);
+    n_tree[l] = (int)tr[l].size();
+  }
+  YQ_HIP(hipStreamSynchronize(s));   // the host lists above are released on return
+}
+
+void FmmForest::apply(const int* mask, const double* V, const int* col, int64_t T,
+                      hipStream_t s) const {
+  if (nmem == 0) return;
+  const int use_col = p <= kColMaxOrder;
+  const int RT = R16 / 16;
+  if (n_gather)
+    forest_gather_kernel<<<n_gather, 256, 0, s>>>(dev.p, it_gather.p, mask, V, col, T);
+  if (n_p2m)
+    forest_p2m_kernel<<<n_p2m, 64, use_col ? (size_t)(p + 2) * 64 * sizeof(double) : 0, s>>>(
+        dev.p, it_p2m.p, mask, p, use_col);
+  YQ_HIP(hipGetLastError());
+#define YQ_FTREE(rt, G) \
+  forest_tree_kernel<rt, G><<<n_tree[l], 256, 0, s>>>(dev.p, it_tree[l].p, mask, p, l)
+#define YQ_FTREE_ALL(G)                 \
+  switch (RT) {                         \
+    case 1: YQ_FTREE(1, G); break;      \
+    case 2: YQ_FTREE(2, G); break;      \
+    case 3: YQ_FTREE(3, G); break;      \
+    case 4: YQ_FTREE(4, G); break;      \
+    case 5: YQ_FTREE(5, G); break;      \
+    case 6: YQ_FTREE(6, G); break;      \
+    default: YQ_FTREE(7, G); break;     \
+  }
+  for (int l = depth - 1; l >= 2; --l)
+    if (n_tree[l]) YQ_FTREE_ALL(true)
+  YQ_HIP(hipGetLastError());
+  if (n_m2l) {
+#define YQ_FM2L(T)                                                                              \
+  forest_pack_kernel<T><<<n_pack, 256, 0, s>>>(dev.p, it_pack.p, mask, p, R16);                 \
+  switch (RT) {                                                                                 \
+    case 1: forest_m2l_kernel<T, 1><<<n_m2l, 256, 0, s>>>(dev.p, it_m2l.p, mask, p); break;     \
+    case 2: forest_m2l_kernel<T, 2><<<n_m2l, 256, 0, s>>>(dev.p, it_m2l.p, mask, p); break;     \
+    case 3: forest_m2l_kernel<T, 3><<<n_m2l, 256, 0, s>>>(dev.p, it_m2l.p, mask, p); break;     \
+    case 4: forest_m2l_kernel<T, 4><<<n_m2l, 256, 0, s>>>(dev.p, it_m2l.p, mask, p); break;     \
+    case 5: forest_m2l_kernel<T, 5><<<n_m2l, 256, 0, s>>>(dev.p, it_m2l.p, mask, p); break;     \
+    case 6: forest_m2l_kernel<T, 6><<<n_m2l, 256, 0, s>>>(dev.p, it_m2l.p, mask, p); break;     \
+    default: forest_m2l_kernel<T, 7><<<n_m2l, 256, 0, s>>>(dev.p, it_m2l.p, mask, p); break;    \
+  }
+    if (m2l32) {
+      YQ_FM2L(float)
+    } else {
+      YQ_FM2L(double)
+    }
+#undef YQ_FM2L
+    YQ_HIP(hipGetLastError());
+  }
+  for (int l = 2; l < depth; ++l)
+    if (n_tree[l]) YQ_FTREE_ALL(false)
+#undef YQ_FTREE_ALL
+#undef YQ_FTREE
+  YQ_HIP(hipGetLastError());
+  if (n_leaf2) {
+    auto k = f32 ? forest_leaf_kernel<true, 2> : forest_leaf_kernel<false, 2>;
+    k<<<n_leaf2, FB * 2, leaf_lds_bytes(2, p, use_col), s>>>(dev.p, it_leaf2.p, mask, p, use_col);
+  }
+  if (n_leaf4) {
+    auto k = f32 ? forest_leaf_kernel<true, PW> : forest_leaf_kernel<false, PW>;
+    k<<<n_leaf4, FB * PW, leaf_lds_bytes(PW, p, use_col), s>>>(dev.p, it_leaf4.p, mask, p,
+                                                               use_col);
+  }
   YQ_HIP(hipGetLastError());
 }
 

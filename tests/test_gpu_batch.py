@@ -1,5 +1,6 @@
 """Batched solves (many configurations per fused launch) against the oracle, against
-the single-configuration path, and alone vs in a mix."""
+the single-configuration path, and alone vs in a mix; FMM configurations as trees
+of the engine's forest (the default) and as worker-thread problems."""
 import numpy as np
 import pytest
 
@@ -166,7 +167,8 @@ def test_batch_fmm_lane_matches_oracle_single_and_direct_batch(oracles):
     cfgs = _configs()
     prm = dict(panels_per_particle=P, qbx_order=ORDER, tol=1e-10, precision=1)
     b = yq.Batch(yq.default_params(**prm))
-    b.set_fmm(5 * P * 16, workers=2)        # the 5-particle configuration takes the FMM lane
+    # the 5-particle configuration takes the FMM, as a worker-thread problem
+    b.set_fmm(5 * P * 16, workers=2, in_engine=False)
     b.set_configs(cfgs)
     with pytest.raises(yq.YQError):
         b.set_fmm(0)                         # only before set_configs
@@ -200,6 +202,7 @@ def test_batch_fmm_lane_matches_oracle_single_and_direct_batch(oracles):
     assert np.abs(_np(F) - _np(Fd)).max() < 1e-9 * sc and np.abs(_np(T) - _np(Td)).max() < 1e-9 * sc
     # every configuration in the lane (no engine members)
     allf = yq.Batch(yq.default_params(far_mode=yq.YQ_FAR_FMM, **prm))
+    allf.set_fmm(0, workers=2, in_engine=False)
     allf.set_configs(cfgs[:2])
     allf.set_boundary_data(allf.boundary_label())
     sa, ia = allf.solve()
@@ -208,24 +211,92 @@ def test_batch_fmm_lane_matches_oracle_single_and_direct_batch(oracles):
         assert ia[c]["residual"] <= 1e-10 and _rel(_np(sa)[s], oracles[c]["sigma"]) < 1e-8
 
 
-def _lane_batch(cfgs, graphs, **prm):
+def _lane_batch(cfgs, graphs, in_engine=True, **prm):
     b = yq.Batch(yq.default_params(**prm))
-    b.set_fmm(5 * P * 16, workers=2)        # the 5-particle configuration takes the FMM lane
+    # the 5-particle configuration takes the FMM (a forest tree, or a lane problem)
+    b.set_fmm(5 * P * 16, workers=2, in_engine=in_engine)
     b.set_configs(cfgs)
     b.use_graphs(graphs)
     return b
 
 
-def test_batch_graph_replay_equals_eager_with_the_fmm_lane_active():
-    # the fused iteration stays graph-captured while lane workers solve beside it
-    _torch()
-    cfgs = _configs()
+def _forest_configs():
+    # two FMM configurations of different tree depths between direct members
+    return _configs() + [workloads.random_ellipses(9, 16.0, 0.9, seed=4)]
+
+
+def test_batch_fmm_forest_matches_oracle_single_path_and_alone(oracles):
+    torch = _torch()
+    cfgs = _forest_configs()
+    orc = list(oracles)
+    d = oracle.discretize(cfgs[4], Params(panels=P, qbx_order=ORDER))
+    A4 = oracle.build_matrices(d)
+    f4 = oracle.arc_label(d)
+    orc.append(dict(d=d, A=A4, f=f4, sigma=oracle.lu_solve(A4, f4)))
     prm = dict(panels_per_particle=P, qbx_order=ORDER, tol=1e-10, precision=1)
-    e = _lane_batch(cfgs, False, **prm)
+    b = _lane_batch(cfgs, True, **prm)
+    b.set_boundary_data(b.boundary_label())
+    sig, infos = b.solve()
+    sig = _np(sig)
+    direct = _batch(cfgs[:4], tol=1e-10, precision=1)
+    direct.set_boundary_data(direct.boundary_label())
+    sd = _np(direct.solve()[0])
+    x = np.concatenate([workloads.random_density(o["d"].N, 60 + c) for c, o in enumerate(orc)])
+    op32 = _np(b.apply_operator(x, yq.YQ_MIXED))
+    op64 = _np(b.apply_operator(x, yq.YQ_FP64))
+    for c, o in enumerate(orc):
+        s = slice(int(b.offsets[c]), int(b.offsets[c + 1]))
+        assert infos[c]["residual"] <= 1e-10, (c, infos[c])
+        assert _rel(sig[s], o["sigma"]) < 1e-8, c
+        if c in (2, 4):
+            # forest trees: the inner operator is the standalone FMM problem's, and
+            # the FP64 one the order-40 FMM's (operator error ~1e-10)
+            pb = yq.Problem(yq.default_params(far_mode=yq.YQ_FAR_FMM, **prm))
+            pb.set_workload(cfgs[c])
+            assert _rel(op32[s], _np(pb.apply_operator(x[s], yq.YQ_MIXED))) < 1e-13, c
+            assert _rel(op64[s], o["A"] @ x[s]) < 1e-9, c
+            pb.set_boundary_data(pb.boundary_label())
+            ss, _ = pb.solve()
+            assert _rel(sig[s], _np(ss)) < 1e-8, c
+            # alone (a batch of one tree) = in the mix, bitwise
+            alone = _lane_batch([cfgs[c]], True, **prm)
+            alone.set_boundary_data(alone.boundary_label())
+            sa, ia = alone.solve()
+            assert np.array_equal(_np(sa), sig[s]), c
+            assert ia[0]["iterations"] == infos[c]["iterations"], c
+        else:
+            assert np.array_equal(sd[s], sig[s]), c          # direct members: unchanged
+            assert _rel(op64[s], o["A"] @ x[s]) < 1e-12, c
+    F, T, E = b.forces(torch.as_tensor(sig, device="cuda"))
+    Fd, Td, Ed = direct.forces(torch.as_tensor(sig[:int(b.offsets[4])], device="cuda"))
+    n4 = int(sum(c.center.shape[0] for c in cfgs[:4]))
+    sc = max(np.abs(_np(Fd)).max(), np.abs(_np(Td)).max())
+    assert np.abs(_np(F)[:n4] - _np(Fd)).max() < 1e-9 * sc
+    assert np.abs(_np(T)[:n4] - _np(Td)).max() < 1e-9 * sc
+    # every configuration a tree (no direct members), in FP64 precision too
+    for precision, tol, bound in ((1, 1e-10, 1e-8), (0, 1e-11, 1e-8)):
+        allf = yq.Batch(yq.default_params(far_mode=yq.YQ_FAR_FMM, panels_per_particle=P,
+                                          qbx_order=ORDER, tol=tol, precision=precision))
+        allf.set_configs([cfgs[0], cfgs[4]])
+        allf.set_boundary_data(allf.boundary_label())
+        sa, ia = allf.solve()
+        for k, c in enumerate((0, 4)):
+            s = slice(int(allf.offsets[k]), int(allf.offsets[k + 1]))
+            assert ia[k]["residual"] <= tol and _rel(_np(sa)[s], orc[c]["sigma"]) < bound
+
+
+@pytest.mark.parametrize("in_engine", [True, False])
+def test_batch_graph_replay_equals_eager_with_fmm_configurations(in_engine):
+    # the fused iteration stays graph-captured with forest trees in it, or while
+    # lane workers solve beside it
+    _torch()
+    cfgs = _forest_configs()
+    prm = dict(panels_per_particle=P, qbx_order=ORDER, tol=1e-10, precision=1)
+    e = _lane_batch(cfgs, False, in_engine, **prm)
     e.set_boundary_data(e.boundary_label())
     se, ie = e.solve()
     se = _np(se)
-    g = _lane_batch(cfgs, True, **prm)
+    g = _lane_batch(cfgs, True, in_engine, **prm)
     g.set_boundary_data(g.boundary_label())
     for rep in range(3):
         sg, ig = g.solve()

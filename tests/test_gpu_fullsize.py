@@ -11,8 +11,8 @@
   M2L, the inner operator of the mixed solves) and the order-40 FP64 FMM (the
   refinement residual's far field), against the oracle's rows.
 * A 200-ellipse configuration (the batched workload's largest member size, 8
-  panels per particle) solved inside a batch: density, forces and torques
-  against the oracle's LU.
+  panels per particle) solved inside a batch, with the fused direct far field and
+  as a tree of the FMM forest: density, forces and torques against the oracle's LU.
 """
 import os
 
@@ -114,7 +114,10 @@ def test_c3_fmm_order40_fp64_operator_rows_against_oracle(c3):
     assert err < 5e-10
 
 
-def test_batch_with_a_200_ellipse_member_against_oracle_lu():
+@pytest.mark.parametrize("mode", ["fused", "forest"])
+def test_batch_with_a_200_ellipse_member_against_oracle_lu(mode):
+    # fused: the member's far field is the fused direct sum of the engine's work
+    # list; forest: at 25,600 nodes it takes the FMM, as a tree of the engine's forest
     _torch()
     g = _load("member200_p8.npz")
     member = workloads.batch_member_200()
@@ -123,6 +126,7 @@ def test_batch_with_a_200_ellipse_member_against_oracle_lu():
     cfgs = [small[0], member, small[1], small[2]]
     b = yq.Batch(yq.default_params(panels_per_particle=8, qbx_order=10, tol=1e-9,
                                    precision=yq.YQ_MIXED, restart=60, maxiter=300))
+    b.set_fmm(10 ** 9 if mode == "fused" else 20000)
     b.set_configs(cfgs)
     assert int(b.offsets[2] - b.offsets[1]) == 25600
     f = b.boundary_label()
