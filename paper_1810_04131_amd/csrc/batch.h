@@ -32,11 +32,24 @@ struct ConfDev {
   int kb;         // Krylov reduction blocks
   int64_t kpoff;  // offset of its multi-dot partials
   int fmm;        // far field from the FMM forest (part64, one chunk), not the fused sums
+  // forces: node normals and weights, the particle table, the gradient rows of the
+  // window correction and of the extra near panels, the gradient far-field partials
+  const double* nx;
+  const double* ny;
+  const double* w;
+  const double* pc;
+  const double* WGx;
+  const double* WGy;
+  const double* xgvals;
+  double* gpart;
+  int n;          // particles
+  int64_t poff;   // first particle in the batch's particle order
 };
 
 struct Member {
   yq_problem* pb = nullptr;  // not owned
   int64_t off = 0;
+  int64_t poff = 0;          // first particle in the batch's particle order (forces)
 };
 
 struct Engine {
@@ -59,6 +72,9 @@ struct Engine {
   DevBuf<int> active, inc, jc, kc, conv;
   DevBuf<double> hb, H, cs, sn, gv, yv, scale, bnorm, rtol, res, nrm;
   DevBuf<double> V, w, r, tmp, delta, f;
+  DevBuf<double> gx, gy, pen;   // forces: surface gradient [T], per-particle energies
+  DevBuf<int2> fitems;          // forces: (configuration, particle) blocks
+  int nfitems = 0;
   // members with an FMM far field, as one forest per operator: the inner (FP32
   // leaf pairs and M2L) and the FP64 residual operator (the members' order-40 FMMs)
   FmmForest forest_in, forest_hi;
@@ -98,6 +114,11 @@ struct Engine {
              const std::vector<double>& tolv, std::vector<int>& iters, std::vector<int>& budget,
              std::vector<int>& converged, int& matvecs);
   void solve(std::vector<yq_solve_info>& info, double* x_out);
+  // forces, torques and energy of every member's particles for the density sigma
+  // (arena layout): force [2 P], torque [P] at each member's particle offset;
+  // energy[c] per member (eqs. stress, force_torque, scalar-torque, main)
+  void forces(const double* sigma, double gamma, double* force, double* torque,
+              std::vector<double>& energy);
 };
 
 }  // namespace yq

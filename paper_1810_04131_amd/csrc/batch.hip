@@ -167,6 +167,174 @@ __global__ void bfinish_kernel(const ConfDev* __restrict__ cf, const int* __rest
   out[g] = s + corr;
 }
 
+// ---- batched forces -----------------------------------------------------------------------
+
+// FP64 gradient far field of the direct members (far_grad64_kernel's sums for each
+// (configuration, target block, source chunk) item): gpart[(chunk * 2 + c) * N + i].
+__global__ __launch_bounds__(BB) void bgrad64_kernel(const ConfDev* __restrict__ cf,
+                                                     const int4* __restrict__ items, int nitems,
+                                                     const int* __restrict__ mask,
+                                                     const double* __restrict__ sigma,
+                                                     const double* __restrict__ tab) {
+  __shared__ double2 sxy[BB];
+  __shared__ double2 sq[BB];
+  const int wib = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / FG));
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const int4 w = items[it];
+    const int c = w.x;
+    if (!mask[c]) continue;
+    const ConfDev& cd = cf[c];
+    const int64_t N = cd.N;
+    const double* sg = sigma + cd.off;
+    const int64_t i = (int64_t)w.y * BB + threadIdx.x;
+    const double xi = i < N ? cd.x[i] : 0.0;
+    const double yi = i < N ? cd.y[i] : 0.0;
+    const int64_t j0 = (int64_t)w.z * cd.chunk;
+    const int64_t j1 = min(N, j0 + cd.chunk);
+    const int64_t grp = (int64_t)w.y * (BB / FG) + wib;
+    const bool live = grp * FG < N;
+    double ax = 0.0, ay = 0.0;
+    for (int64_t jb = j0; jb < j1; jb += BB) {
+      const int64_t j = jb + threadIdx.x;
+      __syncthreads();
+      if (j < j1) {
+        const double s = sg[j];
+        sxy[threadIdx.x] = make_double2(cd.x[j], cd.y[j]);
+        sq[threadIdx.x] = make_double2(cd.wnx[j] * s, cd.wny[j] * s);
+      }
+      __syncthreads();
+      const int nb = (int)min((int64_t)BB, j1 - jb);
+      const int tcls = live ? far64_class(cd.f32.grp, cd.f32.tile, grp, jb / FT, cd.kappa)
+                            : C64_GENERAL;
+      for (int q = 0; q < nb;) {
+        const bool split = tcls == C64_GENERAL && live;
+        const int cls = split ? far64_class(cd.f32.grp, cd.f32.pan, grp, (jb + q) / Q, cd.kappa)
+                              : tcls;
+        const int len = split ? Q : nb - q;
+        far_grad64_class_tile(cls, xi, yi, sxy + q, sq + q, len, cd.kap2, tab, ax, ay);
+        q += len;
+      }
+    }
+    if (i < N) {
+      cd.gpart[((int64_t)w.z * 2 + 0) * N + i] = ax;
+      cd.gpart[((int64_t)w.z * 2 + 1) * N + i] = ay;
+    }
+  }
+}
+
+// Surface gradient of every masked node: the chunk sums of the gradient far field
+// (one chunk for a forest tree) and the exterior QBX window and extra-row
+// corrections, in finish_grad_kernel's order.
+__global__ void bfinish_grad_kernel(const ConfDev* __restrict__ cf,
+                                    const int* __restrict__ node_conf, int64_t T,
+                                    const int* __restrict__ mask, const double* __restrict__ sigma,
+                                    double* __restrict__ gx, double* __restrict__ gy) {
+  const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (g >= T) return;
+  const int c = node_conf[g];
+  if (c < 0 || !mask[c]) return;
+  const ConfDev& cd = cf[c];
+  const int64_t N = cd.N;
+  const int64_t i = g - cd.off;
+  const double* sgc = sigma + cd.off;
+  double sx = 0.0, sy = 0.0;
+  for (int k = 0; k < cd.chunks; ++k) {
+    sx += cd.gpart[((int64_t)k * 2 + 0) * N + i];
+    sy += cd.gpart[((int64_t)k * 2 + 1) * N + i];
+  }
+  const double sc = cd.kappa * cd.kappa / (2.0 * PI);
+  sx *= sc;
+  sy *= sc;
+  const int64_t pan = i / Q;
+  const int64_t pid = pan / cd.P;
+  const int k = (int)(pan % cd.P);
+  for (int sl = 0; sl <= 2 * cd.win; ++sl) {
+    int kj = (k + sl - cd.win) % cd.P;
+    if (kj < 0) kj += cd.P;
+    const double* sg = sgc + (pid * cd.P + kj) * Q;
+    const double* wx = cd.WGx + (int64_t)sl * Q * N + i;
+    const double* wy = cd.WGy + (int64_t)sl * Q * N + i;
+#pragma unroll
+    for (int m = 0; m < Q; ++m) {
+      sx = fma(wx[(int64_t)m * N], sg[m], sx);
+      sy = fma(wy[(int64_t)m * N], sg[m], sy);
+    }
+  }
+  for (int e = cd.xrow[i]; e < cd.xrow[i + 1]; ++e) {
+    const double* sg = sgc + (int64_t)cd.xpan[e] * Q;
+    for (int m = 0; m < Q; ++m) {
+      sx = fma(cd.xgvals[((int64_t)e * 2 + 0) * Q + m], sg[m], sx);
+      sy = fma(cd.xgvals[((int64_t)e * 2 + 1) * Q + m], sg[m], sy);
+    }
+  }
+  gx[g] = sx;
+  gy[g] = sy;
+}
+
+constexpr int FRB = 256;   // forces block (the single-problem forces kernel's)
+
+__device__ __forceinline__ double fsum(double v, double* sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int o = FRB / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+// Traction (eq. stress) integrated per particle (eqs. force_torque, scalar-torque)
+// and the energy of eq. main, one block per (configuration, particle) item, in the
+// single-problem forces kernel's order; f: the boundary data (arena layout).
+__global__ __launch_bounds__(FRB) void bforces_kernel(const ConfDev* __restrict__ cf,
+                                                      const int2* __restrict__ items,
+                                                      const double* __restrict__ f,
+                                                      const double* __restrict__ gx,
+                                                      const double* __restrict__ gy,
+                                                      double gamma, double* __restrict__ force,
+                                                      double* __restrict__ torque,
+                                                      double* __restrict__ energy) {
+  __shared__ double sh[FRB];
+  const int2 it = items[blockIdx.x];
+  const ConfDev& cd = cf[it.x];
+  const int p = it.y;
+  const int64_t b = (int64_t)p * cd.P * Q;
+  const int64_t e = b + (int64_t)cd.P * Q;
+  const double cx = cd.pc[5 * p], cy = cd.pc[5 * p + 1];
+  const double kap = cd.kappa;
+  const double* fc = f + cd.off;
+  const double* gxc = gx + cd.off;
+  const double* gyc = gy + cd.off;
+  double fx = 0.0, fy = 0.0, tq = 0.0, en = 0.0;
+  for (int64_t i = b + threadIdx.x; i < e; i += FRB) {
+    const double ux = gxc[i], uy = gyc[i];
+    const double nx = cd.nx[i], ny = cd.ny[i];
+    const double un = ux * nx + uy * ny;
+    const double iso = gamma * (kap * fc[i] * fc[i] + (ux * ux + uy * uy) / kap);
+    const double c2 = 2.0 * gamma / kap * un;
+    const double tx = iso * nx - c2 * ux;
+    const double ty = iso * ny - c2 * uy;
+    const double w = cd.w[i];
+    fx += w * tx;
+    fy += w * ty;
+    tq += w * ((cd.x[i] - cx) * ty - (cd.y[i] - cy) * tx);
+    en += -gamma / kap * w * fc[i] * un;
+  }
+  fx = fsum(fx, sh);
+  fy = fsum(fy, sh);
+  tq = fsum(tq, sh);
+  en = fsum(en, sh);
+  if (threadIdx.x == 0) {
+    const int64_t q = cd.poff + p;
+    force[2 * q] = fx;
+    force[2 * q + 1] = fy;
+    torque[q] = tq;
+    energy[q] = en;
+  }
+}
+
 // ---- batched Krylov kernels -------------------------------------------------------------------
 
 __device__ __forceinline__ double bsum(double v, double* sh) {
@@ -366,6 +534,8 @@ void Engine::rebuild() {
   std::vector<int4> it;
   std::vector<int2> kb;
   std::vector<FmmForest::Tree> tin, thi;
+  std::vector<int2> fi;
+  int64_t npart = 0;
   int64_t kpoff = 0;
   for (int c = 0; c < nc; ++c) {
     Member& mb = members[c];
@@ -403,17 +573,37 @@ void Engine::rebuild() {
         YQ_REQUIRE(pb->fmm_hi, YQ_EINVAL, "an FMM member of the batch engine needs fmm_resid_order > 0");
         d.fmm = 1;
         d.chunks = 1;
-        tin.push_back(FmmForest::Tree{pb->fmm.get(), c, mb.off, pb->partial.p, pb->tab.p});
-        thi.push_back(FmmForest::Tree{pb->fmm_hi.get(), c, mb.off, pb->partial.p, pb->tab.p});
+        pb->gpartial.reserve((size_t)2 * pb->N);
+        tin.push_back(FmmForest::Tree{pb->fmm.get(), c, mb.off, pb->partial.p, nullptr, pb->tab.p});
+        thi.push_back(FmmForest::Tree{pb->fmm_hi.get(), c, mb.off, pb->partial.p, pb->gpartial.p,
+                                      pb->tab.p});
       } else {
+        pb->gpartial.reserve((size_t)d.chunks * 2 * pb->N);
         for (int t = 0; t < d.tblocks; ++t)
           for (int s = 0; s < d.chunks; ++s) it.push_back(make_int4(c, t, s, 0));
       }
       for (int b = 0; b < d.kb; ++b) kb.push_back(make_int2(c, b));
+      d.nx = pb->nx.p;
+      d.ny = pb->ny.p;
+      d.w = pb->w.p;
+      d.pc = pb->pc.p;
+      d.WGx = pb->WGx.p;
+      d.WGy = pb->WGy.p;
+      d.xgvals = pb->x_total > 0 ? pb->xgvals.p : nullptr;
+      d.gpart = pb->gpartial.p;
+      d.n = pb->n;
+      d.poff = mb.poff;
+      for (int q = 0; q < pb->n; ++q) fi.push_back(make_int2(c, q));
+      npart = std::max<int64_t>(npart, mb.poff + pb->n);
     }
   }
   nitems = (int)it.size();
   nkblk = (int)kb.size();
+  nfitems = (int)fi.size();
+  fitems.alloc(std::max(nfitems, 1));
+  if (nfitems)
+    YQ_HIP(hipMemcpyAsync(fitems.p, fi.data(), nfitems * sizeof(int2), hipMemcpyHostToDevice, stream));
+  pen.alloc(std::max<int64_t>(npart, 1));
   forest_in.build(tin, true, stream);
   forest_hi.build(thi, false, stream);
   conf.alloc(std::max(nc, 1));
@@ -823,6 +1013,39 @@ void Engine::gmres(int prec, const double* b, double* x, const std::vector<int>&
     int any = 0;
     for (int c = 0; c < nc; ++c) any += part[c];
     if (!any) break;
+  }
+}
+
+// Forces of every member: the gradient far field (direct members' fused FP64 sums,
+// the trees' FP64 forest), the surface gradient with its QBX corrections, the
+// per-particle traction integrals, then each member's energy summed on the host in
+// particle order.
+void Engine::forces(const double* sigma, double gamma, double* force, double* torque,
+                    std::vector<double>& energy) {
+  const int nc = (int)members.size();
+  energy.assign(nc, 0.0);
+  if (nc == 0) return;
+  std::vector<int> all(nc, 0);
+  for (int c = 0; c < nc; ++c) all[c] = members[c].pb ? 1 : 0;
+  upload_mask(inc, all);
+  gx.reserve(std::max<int64_t>(T, 1));
+  gy.reserve(std::max<int64_t>(T, 1));
+  if (nitems)
+    bgrad64_kernel<<<grid_blocks(), BB, 0, stream>>>(conf.p, items.p, nitems, inc.p, sigma, tab64.p);
+  forest_hi.apply_grad(inc.p, sigma, nullptr, T, stream);
+  bfinish_grad_kernel<<<nb256(T), 256, 0, stream>>>(conf.p, node_conf.p, T, inc.p, sigma, gx.p, gy.p);
+  if (nfitems)
+    bforces_kernel<<<nfitems, FRB, 0, stream>>>(conf.p, fitems.p, f.p, gx.p, gy.p, gamma, force,
+                                                torque, pen.p);
+  YQ_HIP(hipGetLastError());
+  std::vector<double> e(pen.n);
+  YQ_HIP(hipMemcpyAsync(e.data(), pen.p, pen.n * sizeof(double), hipMemcpyDeviceToHost, stream));
+  YQ_HIP(hipStreamSynchronize(stream));
+  for (int c = 0; c < nc; ++c) {
+    if (!members[c].pb) continue;
+    double t = 0.0;
+    for (int q = 0; q < members[c].pb->n; ++q) t += e[members[c].poff + q];
+    energy[c] = t;
   }
 }
 

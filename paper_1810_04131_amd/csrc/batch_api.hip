@@ -36,7 +36,6 @@ struct yq_batch {
   bool fmm_in_engine = true;
   std::vector<int> direct_idx;            // engine members (fused sums or forest trees)
   std::vector<int> fmm_idx;               // worker-thread (lane) configurations
-  std::vector<int> forest_idx;            // engine members with the FMM (largest first)
   std::vector<hipStream_t> streams;       // one per worker (default priority)
   int device = 0;
   ~yq_batch() {
@@ -78,15 +77,12 @@ void sync_lane(yq_batch* b) {
   for (int c : b->fmm_idx) YQ_HIP(hipStreamSynchronize(b->probs[c]->stream));
 }
 
-// Runs job(c, pb) for every configuration c of idx on the worker threads (in
-// order, from a shared queue), each problem on its worker's stream, while local()
-// runs on this thread; then waits for the workers and raises the first failure
-// (codes other than YQ_OK and YQ_ENOCONV).  restore: the problems go back to the
-// engine's stream afterwards (engine members lent to a worker; job must leave its
-// problem's stream idle, as the synchronous entry points do).
+// Runs job(c, pb) for every configuration c of idx (the FMM lane's problems) on
+// the worker threads (in order, from a shared queue), each problem on its worker's
+// stream, while local() runs on this thread; then waits for the workers and raises
+// the first failure (codes other than YQ_OK and YQ_ENOCONV).
 template <class Job, class Local>
-void run_workers(yq_batch* b, const std::vector<int>& idx, bool restore, Job&& job,
-                 Local&& local) {
+void run_workers(yq_batch* b, const std::vector<int>& idx, Job&& job, Local&& local) {
   const int nf = (int)idx.size();
   std::vector<int> codes(nf, YQ_OK);
   std::vector<std::string> errs(nf);
@@ -103,7 +99,6 @@ void run_workers(yq_batch* b, const std::vector<int>& idx, bool restore, Job&& j
           const int st = job(c, pb);
           codes[k] = st;
           if (st != YQ_OK && st != YQ_ENOCONV) errs[k] = yq_last_error(pb);
-          if (restore) pb->stream = b->eng.stream;
         }
       }));
     }
@@ -175,7 +170,6 @@ int yq_batch_set_configs(yq_batch* b, int32_t nconf, const int32_t* np, const do
     b->eng.members.clear();
     b->direct_idx.clear();
     b->fmm_idx.clear();
-    b->forest_idx.clear();
     b->offsets.assign(nconf + 1, 0);
     b->poffsets.assign(nconf + 1, 0);
     int64_t pofs = 0;
@@ -200,7 +194,6 @@ int yq_batch_set_configs(yq_batch* b, int32_t nconf, const int32_t* np, const do
         pb->batch_member = true;
         pb->stream = b->eng.stream;
         b->direct_idx.push_back(c);
-        if (tree) b->forest_idx.push_back(c);
       }
       st = yq_set_particles(pb, np[c], center_xy + 2 * pofs, angle + pofs, semi_axes + 2 * pofs,
                             kappa[c]);
@@ -214,7 +207,8 @@ int yq_batch_set_configs(yq_batch* b, int32_t nconf, const int32_t* np, const do
       b->poffsets[c + 1] = pofs;
     }
     b->eng.T = b->offsets[nconf];
-    for (int c : b->direct_idx) b->eng.members.push_back(Member{b->probs[c].get(), b->offsets[c]});
+    for (int c : b->direct_idx)
+      b->eng.members.push_back(Member{b->probs[c].get(), b->offsets[c], b->poffsets[c]});
     if (!b->direct_idx.empty()) b->eng.rebuild();
     // worker threads take the largest configurations first; one stream per worker
     auto largest_first = [&](int x, int y) {
@@ -222,9 +216,7 @@ int yq_batch_set_configs(yq_batch* b, int32_t nconf, const int32_t* np, const do
       return nx != ny ? nx > ny : x < y;
     };
     std::sort(b->fmm_idx.begin(), b->fmm_idx.end(), largest_first);
-    std::sort(b->forest_idx.begin(), b->forest_idx.end(), largest_first);
-    const int nw = std::min<int>(b->fmm_workers,
-                                 (int)std::max(b->fmm_idx.size(), b->forest_idx.size()));
+    const int nw = std::min<int>(b->fmm_workers, (int)b->fmm_idx.size());
     while ((int)b->streams.size() < nw) {
       hipStream_t s = nullptr;
       YQ_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
@@ -305,7 +297,7 @@ int yq_batch_solve(yq_batch* b, double* sigma, yq_solve_info* info) {
     // capture overlaps the workers' allocations
     if (!b->direct_idx.empty()) b->eng.ensure_graphs();
     run_workers(
-        b, b->fmm_idx, false,
+        b, b->fmm_idx,
         [&](int c, yq_problem* pb) {
           return yq_solve(pb, nullptr, sigma + b->offsets[c], &all[c]);
         },
@@ -333,25 +325,20 @@ int yq_batch_forces(yq_batch* b, const double* sigma, double gamma, double* forc
     YQ_REQUIRE(b->have_f, YQ_ESTATE, "boundary data not set");
     YQ_REQUIRE(sigma && force && torque, YQ_EINVAL, "null argument");
     std::vector<double> en(b->probs.size(), 0.0);
-    auto one = [&](int c, yq_problem* pb) {
-      return yq_forces(pb, sigma + b->offsets[c], gamma, force + 2 * b->poffsets[c],
-                       torque + b->poffsets[c], &en[c]);
-    };
-    // the FMM configurations' gradient passes on the worker threads (the lane's,
-    // or the forest trees' lent from the engine's stream), the others' here
-    YQ_HIP(hipStreamSynchronize(b->eng.stream));
-    std::vector<char> on_worker(b->probs.size(), 0);
-    for (int c : b->forest_idx) on_worker[c] = 1;
-    // (a batch's FMM configurations are all lane problems or all forest trees)
-    const std::vector<int>& widx = b->fmm_idx.empty() ? b->forest_idx : b->fmm_idx;
-    run_workers(b, widx, b->fmm_idx.empty(), one, [&] {
-      for (int c : b->direct_idx) {
-        if (b->fmm_idx.empty() && on_worker[c]) continue;
-        yq_problem* pb = b->probs[c].get();
-        const int st = one(c, pb);
-        YQ_REQUIRE(st == YQ_OK, st, yq_last_error(pb));
-      }
-    });
+    // the lane problems' forces on the worker threads; the engine members' (fused
+    // sums and forest trees) as one batched pass here
+    run_workers(
+        b, b->fmm_idx,
+        [&](int c, yq_problem* pb) {
+          return yq_forces(pb, sigma + b->offsets[c], gamma, force + 2 * b->poffsets[c],
+                           torque + b->poffsets[c], &en[c]);
+        },
+        [&] {
+          if (b->direct_idx.empty()) return;
+          std::vector<double> ee;
+          b->eng.forces(sigma, gamma, force, torque, ee);
+          for (size_t k = 0; k < ee.size(); ++k) en[b->direct_idx[k]] = ee[k];
+        });
 
     if (energy)
       for (size_t c = 0; c < en.size(); ++c) energy[c] = en[c];

@@ -131,6 +131,7 @@ struct FmmDev {
   const int2* m2l_tiles;
   const double* tab;
   double* out;             // far field of the member's nodes, node order (2 pi / kappa^2 scaling)
+  double* gout;            // its gradient [2 N] (x, then y), the gradient kernels' scaling
 };
 
 // Many quadtrees (one per batch configuration, all of one expansion order) whose
@@ -145,7 +146,7 @@ struct FmmForest {
   int nmem = 0;
   DevBuf<FmmDev> dev;
   // work items (member, index within the member's launch of that pass)
-  DevBuf<int2> it_gather, it_p2m, it_pack, it_m2l, it_leaf2, it_leaf4;
+  DevBuf<int2> it_gather, it_p2m, it_pack, it_m2l, it_leaf2, it_leaf4, it_leaves;
   std::vector<DevBuf<int2>> it_tree;   // per parent level l: M2M into / L2L out of level l
   int n_gather = 0, n_p2m = 0, n_pack = 0, n_m2l = 0, n_leaf2 = 0, n_leaf4 = 0;
   std::vector<int> n_tree;
@@ -158,6 +159,7 @@ struct FmmForest {
     int cfg;
     int64_t off;
     double* out;
+    double* gout;   // gradient output [2 N] (FP64 forests; may be null otherwise)
     const double* tab;
   };
   // p2p32: FP32 leaf pairs (and FP32 M2L where the trees were set up for it), as
@@ -166,6 +168,12 @@ struct FmmForest {
   void build(const std::vector<Tree>& trees, bool p2p32, hipStream_t s);
   // far field of every masked member for the density V + col[cfg] * T + off
   void apply(const int* mask, const double* V, const int* col, int64_t T, hipStream_t s) const;
+  // its gradient (FP64 forests), as Fmm::apply_grad of each tree
+  void apply_grad(const int* mask, const double* V, const int* col, int64_t T,
+                  hipStream_t s) const;
+  // the passes up to the local expansions (gather, P2M, M2M, M2L, L2L)
+  void expansions(const int* mask, const double* V, const int* col, int64_t T,
+                  hipStream_t s) const;
 };
 
 }  // namespace yq

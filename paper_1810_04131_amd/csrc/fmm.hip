@@ -795,31 +795,30 @@ __global__ __launch_bounds__(FB * NW) void l2p_p2p_kernel(int p, double kappa, i
 // since (d/dx + i d/dy) I_n(kappa rho) e^{i n theta} = kappa I_{n+1} e^{i(n+1) theta} for
 // every integer n (I_{-n} = I_n).  Writes gpart[node] (x) and gpart[N + node] (y) in
 // the gradient far-field kernels' scaling.
-__global__ __launch_bounds__(FB * PW) void l2p_p2p_grad_kernel(int p, int use_col, double kappa,
-                                                          const int* __restrict__ ls,
-                                                          const int* __restrict__ lc,
-                                                          const int* __restrict__ gid,
-                                                          const int* __restrict__ nbp,
-                                                          const int* __restrict__ nbi,
-                                                          const double* __restrict__ ccx,
-                                                          const double* __restrict__ ccy,
-                                                          const double2* __restrict__ L,
-                                                          const double* __restrict__ xs,
-                                                          const double* __restrict__ ys,
-                                                          const double* __restrict__ qx,
-                                                          const double* __restrict__ qy,
-                                                          const int* __restrict__ perm, int64_t N,
-                                                          const double* __restrict__ tab,
-                                                          double* __restrict__ gpart) {
+// Leaf b; sh: the kernel's dynamic LDS (leaf_grad_lds_bytes).
+__device__ __forceinline__ void leaf_grad_pass(int b, int p, int use_col, double kappa,
+                                               const int* __restrict__ ls,
+                                               const int* __restrict__ lc,
+                                               const int* __restrict__ gid,
+                                               const int* __restrict__ nbp,
+                                               const int* __restrict__ nbi,
+                                               const double* __restrict__ ccx,
+                                               const double* __restrict__ ccy,
+                                               const double2* __restrict__ L,
+                                               const double* __restrict__ xs,
+                                               const double* __restrict__ ys,
+                                               const double* __restrict__ qx,
+                                               const double* __restrict__ qy,
+                                               const int* __restrict__ perm, int64_t N,
+                                               const double* __restrict__ tab,
+                                               double* __restrict__ gpart, double* sh) {
   // the neighbour leaves are split over PW wavefronts as in l2p_p2p_kernel
-  extern __shared__ double sh[];
   const int lane = threadIdx.x % FB, w = threadIdx.x / FB;
   double2* sbase = reinterpret_cast<double2*>(sh);
   double2* sxy = sbase + w * FB;                              // [PW][FB]
   double2* sq = sbase + (PW + w) * FB;                        // [PW][FB]
   double2* red = sbase + 2 * PW * FB;                         // [PW][FB] wave sums (x, y)
   double* col = reinterpret_cast<double*>(red + PW * FB) + lane;   // [(p + 2) * 64] scaled I_n
-  const int b = blockIdx.x;
   const int s0 = ls[b], cnt = lc[b];
   const double kap2 = kappa * kappa;
   const double cx = ccx[b], cy = ccy[b];
@@ -882,6 +881,27 @@ __global__ __launch_bounds__(FB * PW) void l2p_p2p_grad_kernel(int p, int use_co
     }
     __syncthreads();   // red is rewritten by the next group of targets
   }
+}
+
+__global__ __launch_bounds__(FB * PW) void l2p_p2p_grad_kernel(int p, int use_col, double kappa,
+                                                          const int* __restrict__ ls,
+                                                          const int* __restrict__ lc,
+                                                          const int* __restrict__ gid,
+                                                          const int* __restrict__ nbp,
+                                                          const int* __restrict__ nbi,
+                                                          const double* __restrict__ ccx,
+                                                          const double* __restrict__ ccy,
+                                                          const double2* __restrict__ L,
+                                                          const double* __restrict__ xs,
+                                                          const double* __restrict__ ys,
+                                                          const double* __restrict__ qx,
+                                                          const double* __restrict__ qy,
+                                                          const int* __restrict__ perm, int64_t N,
+                                                          const double* __restrict__ tab,
+                                                          double* __restrict__ gpart) {
+  extern __shared__ double sh[];
+  leaf_grad_pass(blockIdx.x, p, use_col, kappa, ls, lc, gid, nbp, nbi, ccx, ccy, L, xs, ys, qx, qy,
+                 perm, N, tab, gpart, sh);
 }
 
 // ---- tree keys (device) ------------------------------------------------------------------
@@ -1530,7 +1550,25 @@ __global__ __launch_bounds__(FB * NW) void forest_leaf_kernel(const FmmDev* __re
                      d.out, sh);
 }
 
+__global__ __launch_bounds__(FB * PW) void forest_leaf_grad_kernel(const FmmDev* __restrict__ fd,
+                                                                  const int2* __restrict__ items,
+                                                                  const int* __restrict__ mask,
+                                                                  int p, int use_col) {
+  extern __shared__ double sh[];
+  const int2 it = items[blockIdx.x];
+  const FmmDev& d = fd[it.x];
+  if (!mask[d.cfg]) return;
+  leaf_grad_pass(it.y, p, use_col, d.kappa, d.leaf_start, d.leaf_cnt, d.leaf_gid, d.nbp, d.nbi,
+                 d.leaf_cx, d.leaf_cy, d.Lall, d.xs, d.ys, d.qx, d.qy, d.perm, d.N, d.tab, d.gout,
+                 sh);
+}
+
 namespace {
+
+size_t leaf_grad_lds_bytes(int p, int use_col) {
+  return (size_t)PW * FB * 3 * sizeof(double2) +
+         (use_col ? (size_t)(p + 2) * 64 * sizeof(double) : 0);
+}
 
 size_t leaf_lds_bytes(int nw, int p, int use_col) {
   return (size_t)nw * FB * (2 * sizeof(double2) + sizeof(float2) + sizeof(double)) +
@@ -1594,6 +1632,7 @@ void FmmForest::build(const std::vector<Tree>& trees, bool p2p32, hipStream_t s)
     d.m2l_tiles = f.m2l_tiles.p;
     d.tab = trees[m].tab;
     d.out = trees[m].out;
+    d.gout = trees[m].gout;
     if (m2l32) {
       f.mpk32.fit((size_t)f.nbox_total * R16);
       d.amat = f.amat32.p;
@@ -1619,6 +1658,8 @@ void FmmForest::build(const std::vector<Tree>& trees, bool p2p32, hipStream_t s)
     auto& lst = f.nleaf >= kLeavesFor2 ? l2 : l4;
     for (int b = 0; b < f.nleaf; ++b) lst.push_back(make_int2(m, b));
   }
+  std::vector<int2> la(l2);   // every leaf (the gradient pass takes PW waves for all)
+  la.insert(la.end(), l4.begin(), l4.end());
   dev.fit(nmem);
   YQ_HIP(hipMemcpyAsync(dev.p, h.data(), nmem * sizeof(FmmDev), hipMemcpyHostToDevice, s));
   upload_items(it_gather, g, s);
@@ -1627,6 +1668,7 @@ void FmmForest::build(const std::vector<Tree>& trees, bool p2p32, hipStream_t s)
   upload_items(it_m2l, ml, s);
   upload_items(it_leaf2, l2, s);
   upload_items(it_leaf4, l4, s);
+  upload_items(it_leaves, la, s);
   n_gather = (int)g.size();
   n_p2m = (int)pm.size();
   n_pack = (int)pk.size();
@@ -1644,6 +1686,36 @@ void FmmForest::build(const std::vector<Tree>& trees, bool p2p32, hipStream_t s)
 
 void FmmForest::apply(const int* mask, const double* V, const int* col, int64_t T,
                       hipStream_t s) const {
+  expansions(mask, V, col, T, s);
+  if (nmem == 0) return;
+  const int use_col = p <= kColMaxOrder;
+  if (n_leaf2) {
+    auto k = f32 ? forest_leaf_kernel<true, 2> : forest_leaf_kernel<false, 2>;
+    k<<<n_leaf2, FB * 2, leaf_lds_bytes(2, p, use_col), s>>>(dev.p, it_leaf2.p, mask, p, use_col);
+  }
+  if (n_leaf4) {
+    auto k = f32 ? forest_leaf_kernel<true, PW> : forest_leaf_kernel<false, PW>;
+    k<<<n_leaf4, FB * PW, leaf_lds_bytes(PW, p, use_col), s>>>(dev.p, it_leaf4.p, mask, p,
+                                                               use_col);
+  }
+  YQ_HIP(hipGetLastError());
+}
+
+void FmmForest::apply_grad(const int* mask, const double* V, const int* col, int64_t T,
+                           hipStream_t s) const {
+  YQ_REQUIRE(!f32, YQ_EINVAL, "FMM forest: the gradient is FP64");
+  expansions(mask, V, col, T, s);
+  if (nmem == 0) return;
+  const int use_col = p <= kColMaxOrder;
+  const int nl = n_leaf2 + n_leaf4;
+  if (nl)
+    forest_leaf_grad_kernel<<<nl, FB * PW, leaf_grad_lds_bytes(p, use_col), s>>>(
+        dev.p, it_leaves.p, mask, p, use_col);
+  YQ_HIP(hipGetLastError());
+}
+
+void FmmForest::expansions(const int* mask, const double* V, const int* col, int64_t T,
+                           hipStream_t s) const {
   if (nmem == 0) return;
   const int use_col = p <= kColMaxOrder;
   const int RT = R16 / 16;
@@ -1692,16 +1764,6 @@ void FmmForest::apply(const int* mask, const double* V, const int* col, int64_t 
     if (n_tree[l]) YQ_FTREE_ALL(false)
 #undef YQ_FTREE_ALL
 #undef YQ_FTREE
-  YQ_HIP(hipGetLastError());
-  if (n_leaf2) {
-    auto k = f32 ? forest_leaf_kernel<true, 2> : forest_leaf_kernel<false, 2>;
-    k<<<n_leaf2, FB * 2, leaf_lds_bytes(2, p, use_col), s>>>(dev.p, it_leaf2.p, mask, p, use_col);
-  }
-  if (n_leaf4) {
-    auto k = f32 ? forest_leaf_kernel<true, PW> : forest_leaf_kernel<false, PW>;
-    k<<<n_leaf4, FB * PW, leaf_lds_bytes(PW, p, use_col), s>>>(dev.p, it_leaf4.p, mask, p,
-                                                               use_col);
-  }
   YQ_HIP(hipGetLastError());
 }
 

@@ -273,6 +273,16 @@ def test_batch_fmm_forest_matches_oracle_single_path_and_alone(oracles):
     sc = max(np.abs(_np(Fd)).max(), np.abs(_np(Td)).max())
     assert np.abs(_np(F)[:n4] - _np(Fd)).max() < 1e-9 * sc
     assert np.abs(_np(T)[:n4] - _np(Td)).max() < 1e-9 * sc
+    # a tree's forces (order-40 FMM gradient, batched) are the standalone FMM problem's
+    poffs = np.concatenate([[0], np.cumsum([c.center.shape[0] for c in cfgs])])
+    for c in (2, 4):
+        pb = yq.Problem(yq.default_params(far_mode=yq.YQ_FAR_FMM, **prm))
+        pb.set_workload(cfgs[c])
+        pb.set_boundary_data(pb.boundary_label())
+        Fs, Ts, Es = pb.forces(b.segment(torch.as_tensor(sig, device="cuda"), c))
+        assert np.array_equal(_np(Fs), _np(F)[poffs[c]:poffs[c + 1]]), c
+        assert np.array_equal(_np(Ts), _np(T)[poffs[c]:poffs[c + 1]]), c
+        assert Es == E[c], c
     # every configuration a tree (no direct members), in FP64 precision too
     for precision, tol, bound in ((1, 1e-10, 1e-8), (0, 1e-11, 1e-8)):
         allf = yq.Batch(yq.default_params(far_mode=yq.YQ_FAR_FMM, panels_per_particle=P,
