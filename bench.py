@@ -514,8 +514,8 @@ def bench_batch(args):
                                   f"iteration for the whole batch: {int((~lane).sum())} below "
                                   f"{thr} nodes with the fused direct far field, {int(lane.sum())} "
                                   f"from {thr} nodes on as trees of the FMM forest (FMM order 20 "
-                                  f"inner / 40 FP64 residuals; forces of the trees on "
-                                  f"{args.fmm_workers} worker threads)" if forest
+                                  f"inner / 40 FP64 residuals); the forces of every "
+                                  f"configuration in one batched pass" if forest
                                   else f"{int((~lane).sum())} configurations below {thr} nodes in the "
                                   f"fused direct engine (graph-replayed iteration), "
                                   f"{int(lane.sum())} from {thr} nodes on in the FMM lane "
