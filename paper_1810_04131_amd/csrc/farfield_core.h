@@ -65,6 +65,7 @@ __device__ __forceinline__ double far64_class_tile(int cls, double xi, double yi
 // FP64 and the difference is rounded to FP32.
 __device__ __forceinline__ float far32_tile(double xi, double yi, const double2* sxy,
                                            const float2* sq, int nb, float kap2, float acc) {
+#pragma unroll 4
   for (int k = 0; k < nb; ++k) {
     const double2 p = sxy[k];
     const float2 q = sq[k];

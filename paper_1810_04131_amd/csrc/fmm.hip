@@ -697,11 +697,15 @@ __device__ __forceinline__ void leaf_pass(int b, int p, double kappa, int use_lo
                                           const int* __restrict__ perm,
                                           const double* __restrict__ tab,
                                           double* __restrict__ partial, double* sh) {
-  const int lane = threadIdx.x % FB, w = threadIdx.x / FB;
+  // the wave index is uniform over the wave: in a scalar register, the neighbour-leaf
+  // and source loops below run on scalar counters (the LDS tiles are addressed from a
+  // vector register, so the unrolled pair loop reads them with immediate offsets)
+  const int lane = threadIdx.x % FB, w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / FB));
+  const int wv = threadIdx.x / FB;
   double2* sbase = reinterpret_cast<double2*>(sh);
-  double2* sxy = sbase + w * FB;                                        // [NW][FB]
-  double2* sq = sbase + (NW + w) * FB;                                  // [NW][FB] (FP64)
-  float2* sq32 = reinterpret_cast<float2*>(sbase + 2 * NW * FB) + w * FB;   // [NW][FB] (FP32)
+  double2* sxy = sbase + wv * FB;                                       // [NW][FB]
+  double2* sq = sbase + (NW + wv) * FB;                                 // [NW][FB] (FP64)
+  float2* sq32 = reinterpret_cast<float2*>(sbase + 2 * NW * FB) + wv * FB;  // [NW][FB] (FP32)
   double* red = reinterpret_cast<double*>(reinterpret_cast<float2*>(sbase + 2 * NW * FB) +
                                           NW * FB);                     // [NW][FB] wave sums
   double* col = red + NW * FB + lane;   // [(p + 1) * 64] scaled I_n, wave 0
@@ -715,8 +719,9 @@ __device__ __forceinline__ void leaf_pass(int b, int p, double kappa, int use_lo
     double acc64 = 0.0;
     float acc32 = 0.0f;
     for (int e = nbp[b] + w; e < nbp[b + 1]; e += NW) {
-      const int nb = nbi[e];
-      const int t0 = ls[nb], tc = lc[nb];
+      const int nb = __builtin_amdgcn_readfirstlane(nbi[e]);
+      const int t0 = __builtin_amdgcn_readfirstlane(ls[nb]);
+      const int tc = __builtin_amdgcn_readfirstlane(lc[nb]);
       for (int k0 = 0; k0 < tc; k0 += FB) {
         wave_sync();   // this wave's reads of the previous tile are done
         if (k0 + lane < tc) {
@@ -813,7 +818,9 @@ __device__ __forceinline__ void leaf_grad_pass(int b, int p, int use_col, double
                                                const double* __restrict__ tab,
                                                double* __restrict__ gpart, double* sh) {
   // the neighbour leaves are split over PW wavefronts as in l2p_p2p_kernel
-  const int lane = threadIdx.x % FB, w = threadIdx.x / FB;
+  // the wave index is uniform over the wave: in a scalar register, the neighbour-leaf
+  // and source loops below run on scalar counters
+  const int lane = threadIdx.x % FB, w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / FB));
   double2* sbase = reinterpret_cast<double2*>(sh);
   double2* sxy = sbase + w * FB;                              // [PW][FB]
   double2* sq = sbase + (PW + w) * FB;                        // [PW][FB]
@@ -828,8 +835,9 @@ __device__ __forceinline__ void leaf_grad_pass(int b, int p, int use_col, double
     const double xi = act ? xs[s0 + j] : cx, yi = act ? ys[s0 + j] : cy;
     double ax = 0.0, ay = 0.0;
     for (int e = nbp[b] + w; e < nbp[b + 1]; e += PW) {
-      const int nb = nbi[e];
-      const int t0 = ls[nb], tc = lc[nb];
+      const int nb = __builtin_amdgcn_readfirstlane(nbi[e]);
+      const int t0 = __builtin_amdgcn_readfirstlane(ls[nb]);
+      const int tc = __builtin_amdgcn_readfirstlane(lc[nb]);
       for (int k0 = 0; k0 < tc; k0 += FB) {
         wave_sync();   // this wave's reads of the previous tile are done
         if (k0 + lane < tc) {
