@@ -418,9 +418,7 @@ def bench_batch(args):
     b.profile(True)      # events around every fused far-field launch (split iteration graphs)
 
     def step():
-        sig, infos = b.solve()
-        F, T, E = b.forces(sig)
-        return sig, infos, F, T, E
+        return b.solve_forces()
 
     for k in range(max(args.warmup, 1)):
         step()

@@ -384,6 +384,13 @@ int yq_batch_apply_operator(yq_batch* batch, const double* sigma, double* out, i
  * YQ_ENOCONV if any configuration missed the tolerance. */
 int yq_batch_solve(yq_batch* batch, double* sigma, yq_solve_info* info);
 
+/* yq_batch_solve, then yq_batch_forces of its sigma, in one call: the FP64
+ * residual expected to be the last one of each mixed solve also gives the gradient
+ * far field of the forces (eq. stress), as yq_solve_forces does for one problem.
+ * Returns the solve's status (YQ_ENOCONV with the forces computed). */
+int yq_batch_solve_forces(yq_batch* batch, double* sigma, yq_solve_info* info, double gamma,
+                          double* force, double* torque, double* energy);
+
 /* Forces and torques of every particle (particles in batch order): dev force
  * [2 * total particles], dev torque [total particles]; host energy [nconf].
  * The FMM lane's configurations run on the worker threads beside the engine's. */

@@ -337,6 +337,24 @@ class Batch:
             self._check(st)
         return out, [{k: getattr(x, k) for k, _ in x._fields_} for x in infos]
 
+    def solve_forces(self, gamma=1.0, allow_noconv=False):
+        """solve() then forces() of its sigma in one call (yq_batch_solve_forces)."""
+        import numpy as np
+        out = self._f64(self.total)
+        n = len(self.offsets) - 1
+        infos = (yq_solve_info * n)()
+        npt = int(self.nparticles.sum())
+        F = self._f64(2 * npt)
+        T = self._f64(npt)
+        E = np.zeros(n)
+        self._sync()
+        st = self.lib.yq_batch_solve_forces(self.h, _ptr(out), infos, float(gamma), _ptr(F), _ptr(T),
+                                            E.ctypes.data_as(ctypes.c_void_p))
+        if not (allow_noconv and st == _lib.YQ_ENOCONV):
+            self._check(st)
+        return (out, [{k: getattr(x, k) for k, _ in x._fields_} for x in infos], F.view(npt, 2), T,
+                E)
+
     def forces(self, sigma, gamma=1.0):
         import numpy as np
         sigma = self._dev(sigma)

@@ -131,6 +131,7 @@ SIGNATURES = {
     "yq_batch_set_boundary_data": (c_int32, [P, P]),
     "yq_batch_apply_operator": (c_int32, [P, P, P, c_int32]),
     "yq_batch_solve": (c_int32, [P, P, P]),
+    "yq_batch_solve_forces": (c_int32, [P, P, P, c_double, P, P, P]),
     "yq_batch_forces": (c_int32, [P, P, c_double, P, P, P]),
     "yq_batch_autotune": (c_int32, [P, ctypes.POINTER(c_int32), ctypes.POINTER(c_int32)]),
     "yq_batch_use_graphs": (c_int32, [P, c_int32]),

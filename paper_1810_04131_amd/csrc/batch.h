@@ -69,7 +69,7 @@ struct Engine {
   DevBuf<int> node_conf;
   int nitems = 0, nkblk = 0;
   DevBuf<double> kpart;
-  DevBuf<int> active, inc, jc, kc, conv;
+  DevBuf<int> active, inc, jc, kc, conv, pmask, fmask;
   DevBuf<double> hb, H, cs, sn, gv, yv, scale, bnorm, rtol, res, nrm;
   DevBuf<double> V, w, r, tmp, delta, f;
   DevBuf<double> gx, gy, pen;   // forces: surface gradient [T], per-particle energies
@@ -113,12 +113,19 @@ struct Engine {
   void gmres(int prec, const double* b, double* x, const std::vector<int>& incl,
              const std::vector<double>& tolv, std::vector<int>& iters, std::vector<int>& budget,
              std::vector<int>& converged, int& matvecs);
-  void solve(std::vector<yq_solve_info>& info, double* x_out);
+  // fuse (mixed precision): the FP64 residual expected to be the last one also
+  // computes the gradient far field for the forces (grad_ok[c] when it holds that of
+  // the returned solution)
+  void solve(std::vector<yq_solve_info>& info, double* x_out, bool fuse = false);
+  std::vector<char> grad_ok;
+  // FP64 operator for plain and fused configurations (fused: with the gradient far field)
+  void resid(const std::vector<int>& plain, const std::vector<int>& fused, const double* x,
+             double* out);
   // forces, torques and energy of every member's particles for the density sigma
   // (arena layout): force [2 P], torque [P] at each member's particle offset;
   // energy[c] per member (eqs. stress, force_torque, scalar-torque, main)
   void forces(const double* sigma, double gamma, double* force, double* torque,
-              std::vector<double>& energy);
+              std::vector<double>& energy, const std::vector<char>* grad_done = nullptr);
 };
 
 }  // namespace yq

@@ -222,6 +222,61 @@ __global__ __launch_bounds__(BB) void bgrad64_kernel(const ConfDev* __restrict__
   }
 }
 
+// The FP64 far field and its gradient in one pass over the pairs
+// (far_fused64_kernel's sums for each item): part64 and gpart.
+__global__ __launch_bounds__(BB) void bfused64_kernel(const ConfDev* __restrict__ cf,
+                                                      const int4* __restrict__ items, int nitems,
+                                                      const int* __restrict__ mask,
+                                                      const double* __restrict__ V,
+                                                      const int* __restrict__ col, int64_t T,
+                                                      const double* __restrict__ tab) {
+  __shared__ double2 sxy[BB];
+  __shared__ double2 sq[BB];
+  const int wib = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / FG));
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const int4 w = items[it];
+    const int c = w.x;
+    if (!mask[c]) continue;
+    const ConfDev& cd = cf[c];
+    const int64_t N = cd.N;
+    const double* sg = V + (col ? (int64_t)col[c] * T : 0) + cd.off;
+    const int64_t i = (int64_t)w.y * BB + threadIdx.x;
+    const double xi = i < N ? cd.x[i] : 0.0;
+    const double yi = i < N ? cd.y[i] : 0.0;
+    const int64_t j0 = (int64_t)w.z * cd.chunk;
+    const int64_t j1 = min(N, j0 + cd.chunk);
+    const int64_t grp = (int64_t)w.y * (BB / FG) + wib;
+    const bool live = grp * FG < N;
+    double acc = 0.0, ax = 0.0, ay = 0.0;
+    for (int64_t jb = j0; jb < j1; jb += BB) {
+      const int64_t j = jb + threadIdx.x;
+      __syncthreads();
+      if (j < j1) {
+        const double s = sg[j];
+        sxy[threadIdx.x] = make_double2(cd.x[j], cd.y[j]);
+        sq[threadIdx.x] = make_double2(cd.wnx[j] * s, cd.wny[j] * s);
+      }
+      __syncthreads();
+      const int nb = (int)min((int64_t)BB, j1 - jb);
+      const int tcls = live ? far64_class(cd.f32.grp, cd.f32.tile, grp, jb / FT, cd.kappa)
+                            : C64_GENERAL;
+      for (int q = 0; q < nb;) {
+        const bool split = tcls == C64_GENERAL && live;
+        const int cls = split ? far64_class(cd.f32.grp, cd.f32.pan, grp, (jb + q) / Q, cd.kappa)
+                              : tcls;
+        const int len = split ? Q : nb - q;
+        far_fused64_class_tile(cls, xi, yi, sxy + q, sq + q, len, cd.kap2, tab, acc, ax, ay);
+        q += len;
+      }
+    }
+    if (i < N) {
+      cd.part64[(int64_t)w.z * N + i] = acc;
+      cd.gpart[((int64_t)w.z * 2 + 0) * N + i] = ax;
+      cd.gpart[((int64_t)w.z * 2 + 1) * N + i] = ay;
+    }
+  }
+}
+
 // Surface gradient of every masked node: the chunk sums of the gradient far field
 // (one chunk for a forest tree) and the exterior QBX window and extra-row
 // corrections, in finish_grad_kernel's order.
@@ -629,6 +684,8 @@ void Engine::rebuild() {
   const bool fresh = active.n != (size_t)std::max(nc, 1);
   active.alloc(std::max(nc, 1));
   inc.alloc(std::max(nc, 1));
+  pmask.alloc(std::max(nc, 1));
+  fmask.alloc(std::max(nc, 1));
   jc.alloc(std::max(nc, 1));
   kc.alloc(std::max(nc, 1));
   conv.alloc(std::max(nc, 1));
@@ -1021,18 +1078,27 @@ void Engine::gmres(int prec, const double* b, double* x, const std::vector<int>&
 // per-particle traction integrals, then each member's energy summed on the host in
 // particle order.
 void Engine::forces(const double* sigma, double gamma, double* force, double* torque,
-                    std::vector<double>& energy) {
+                    std::vector<double>& energy, const std::vector<char>* grad_done) {
   const int nc = (int)members.size();
   energy.assign(nc, 0.0);
   if (nc == 0) return;
-  std::vector<int> all(nc, 0);
-  for (int c = 0; c < nc; ++c) all[c] = members[c].pb ? 1 : 0;
-  upload_mask(inc, all);
+  std::vector<int> all(nc, 0), need(nc, 0);
+  int nneed = 0;
+  for (int c = 0; c < nc; ++c) {
+    all[c] = members[c].pb ? 1 : 0;
+    need[c] = all[c] && !(grad_done && (*grad_done)[c]);
+    nneed += need[c];
+  }
   gx.reserve(std::max<int64_t>(T, 1));
   gy.reserve(std::max<int64_t>(T, 1));
-  if (nitems)
-    bgrad64_kernel<<<grid_blocks(), BB, 0, stream>>>(conf.p, items.p, nitems, inc.p, sigma, tab64.p);
-  forest_hi.apply_grad(inc.p, sigma, nullptr, T, stream);
+  if (nneed) {   // gradient far field of the members whose solve did not leave it
+    upload_mask(pmask, need);
+    if (nitems)
+      bgrad64_kernel<<<grid_blocks(), BB, 0, stream>>>(conf.p, items.p, nitems, pmask.p, sigma,
+                                                       tab64.p);
+    forest_hi.apply_grad(pmask.p, sigma, nullptr, T, stream);
+  }
+  upload_mask(inc, all);
   bfinish_grad_kernel<<<nb256(T), 256, 0, stream>>>(conf.p, node_conf.p, T, inc.p, sigma, gx.p, gy.p);
   if (nfitems)
     bforces_kernel<<<nfitems, FRB, 0, stream>>>(conf.p, fitems.p, f.p, gx.p, gy.p, gamma, force,
@@ -1049,11 +1115,58 @@ void Engine::forces(const double* sigma, double gamma, double* force, double* to
   }
 }
 
+// out = A x (FP64 operator: the direct members' fused FP64 sums, the trees' order-40
+// forest) for the configurations in plain or fused; for those in fused the same pass
+// over the pairs (and the same expansions) also leaves the gradient far field of x in
+// the members' gradient partials.
+void Engine::resid(const std::vector<int>& plain, const std::vector<int>& fused, const double* x,
+                   double* out) {
+  const int nc = (int)members.size();
+  std::vector<int> uni(nc);
+  int nf = 0;
+  for (int c = 0; c < nc; ++c) {
+    uni[c] = plain[c] || fused[c];
+    nf += fused[c];
+  }
+  if (nf == 0) {
+    upload_mask(inc, uni);
+    matvec(YQ_FP64, inc.p, x, nullptr, out);
+    return;
+  }
+  upload_mask(inc, uni);
+  upload_mask(pmask, plain);
+  upload_mask(fmask, fused);
+  forest_hi.expansions(inc.p, x, nullptr, T, stream);
+  forest_hi.leaves(inc.p, stream);
+  forest_hi.leaves_grad(fmask.p, stream);
+  if (nitems) {
+    unsigned long long* pc = prof_on ? prof_pairs.p : nullptr;
+    hipEvent_t a = prof_on ? prof_event() : nullptr;
+    if (a) YQ_HIP(hipEventRecord(a, stream));
+    bfar64_kernel<<<grid_blocks(), BB, 0, stream>>>(conf.p, items.p, nitems, pmask.p, x, nullptr, T,
+                                                    tab64.p, pc);
+    if (a) {
+      hipEvent_t b = prof_event();
+      YQ_HIP(hipEventRecord(b, stream));
+      prof_ev[0].push_back({a, b});
+    }
+    bfused64_kernel<<<grid_blocks(), BB, 0, stream>>>(conf.p, items.p, nitems, fmask.p, x, nullptr,
+                                                      T, tab64.p);
+  }
+  bfinish_kernel<<<nb256(T), 256, 0, stream>>>(conf.p, node_conf.p, T, inc.p, 0, x, nullptr, out);
+  YQ_HIP(hipGetLastError());
+}
+
 // Full solve (FP64 or mixed with refinement) of every member; results in x.
-void Engine::solve(std::vector<yq_solve_info>& info, double* x_out) {
+void Engine::solve(std::vector<yq_solve_info>& info, double* x_out, bool fuse) {
   const int nc = (int)members.size();
   auto t0 = std::chrono::steady_clock::now();
   info.assign(nc, yq_solve_info{});
+  grad_ok.assign(nc, 0);
+  fuse = fuse && prm.precision == YQ_MIXED;
+  // per configuration: the next FP64 residual is expected to meet the tolerance (its
+  // inner solve aimed straight at it), so it also computes the forces' gradient
+  std::vector<int> expect_last(nc, 0);
   std::vector<int> all(nc, 1), iters(nc, 0), budget(nc, prm.maxiter), conv_c(nc, 0);
   for (int c = 0; c < nc; ++c) all[c] = members[c].pb ? 1 : 0;
   int mv = 0;
@@ -1080,7 +1193,14 @@ void Engine::solve(std::vector<yq_solve_info>& info, double* x_out) {
       if (outer == 0) {
         axpby(inc.p, 1.0, f.p, 0.0, nullptr, r.p);
       } else {
-        matvec(YQ_FP64, inc.p, x_out, nullptr, tmp.p);
+        std::vector<int> pl(nc, 0), fu(nc, 0);
+        for (int c = 0; c < nc; ++c) {
+          fu[c] = run[c] && fuse && expect_last[c];
+          pl[c] = run[c] && !fu[c];
+          if (fu[c]) grad_ok[c] = 1;
+        }
+        resid(pl, fu, x_out, tmp.p);
+        upload_mask(inc, run);
         axpby(inc.p, 1.0, f.p, -1.0, tmp.p, r.p);
         for (int c = 0; c < nc; ++c)
           if (run[c]) ++info[c].matvecs_fp64;
@@ -1101,6 +1221,8 @@ void Engine::solve(std::vector<yq_solve_info>& info, double* x_out) {
         ++nrun;
         ++info[c].outer_steps;
         tolv[c] = std::min(0.5, std::max(prm.inner_tol, 0.5 * prm.tol / std::max(rel[c], 1e-300)));
+        grad_ok[c] = 0;   // the inner solve moves x
+        expect_last[c] = rel[c] * tolv[c] <= prm.tol;
       }
       if (!nrun) break;
       // the residual r is the right-hand side of the inner solve; delta -> x
@@ -1126,8 +1248,11 @@ void Engine::solve(std::vector<yq_solve_info>& info, double* x_out) {
     }
   std::vector<double> rn(nc, 0.0);
   if (nneed) {
+    std::vector<int> none(nc, 0);
+    if (fuse)
+      for (int c = 0; c < nc; ++c) grad_ok[c] = grad_ok[c] || need[c];
+    resid(fuse ? none : need, fuse ? need : none, x_out, tmp.p);
     upload_mask(inc, need);
-    matvec(YQ_FP64, inc.p, x_out, nullptr, tmp.p);
     axpby(inc.p, 1.0, f.p, -1.0, tmp.p, r.p);
     dots(inc.p, r.p, r.p);
     rn = read_nrm();

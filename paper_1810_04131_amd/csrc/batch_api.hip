@@ -285,37 +285,77 @@ int yq_batch_apply_operator(yq_batch* b, const double* sigma, double* out, int32
   });
 }
 
-int yq_batch_solve(yq_batch* b, double* sigma, yq_solve_info* info) {
+}  // extern "C"
+
+namespace {
+
+struct ForcesOut {
+  double gamma;
+  double* force;
+  double* torque;
+  double* energy;
+};
+
+// yq_batch_solve, and with fo its forces: the lane problems through
+// yq_solve_forces, the engine's members with the FP64 residual expected to be the
+// last one also giving the gradient far field (no separate gradient pass for them).
+int batch_solve(yq_batch* b, double* sigma, yq_solve_info* info, const ForcesOut* fo) {
   int status = YQ_OK;
   int rc = bguard(b, [&] {
     require(b);
     YQ_REQUIRE(sigma, YQ_EINVAL, "null sigma");
     YQ_REQUIRE(b->have_f, YQ_ESTATE, "boundary data not set");
+    YQ_REQUIRE(!fo || (fo->force && fo->torque), YQ_EINVAL, "null argument");
     const int nconf = (int)b->probs.size();
     std::vector<yq_solve_info> all(nconf);
+    std::vector<double> en(nconf, 0.0);
     // the fused iteration's graphs are captured before any worker starts, so no
     // capture overlaps the workers' allocations
     if (!b->direct_idx.empty()) b->eng.ensure_graphs();
     run_workers(
         b, b->fmm_idx,
         [&](int c, yq_problem* pb) {
-          return yq_solve(pb, nullptr, sigma + b->offsets[c], &all[c]);
+          if (!fo) return yq_solve(pb, nullptr, sigma + b->offsets[c], &all[c]);
+          return yq_solve_forces(pb, nullptr, sigma + b->offsets[c], &all[c], fo->gamma,
+                                 fo->force + 2 * b->poffsets[c], fo->torque + b->poffsets[c],
+                                 &en[c]);
         },
-        [&] {   // fused lane on this thread
+        [&] {   // the engine on this thread
           if (b->direct_idx.empty()) return;
           std::vector<yq_solve_info> inf;
-          b->eng.solve(inf, sigma);
-          YQ_HIP(hipStreamSynchronize(b->eng.stream));
+          b->eng.solve(inf, sigma, fo != nullptr);
           for (size_t k = 0; k < inf.size(); ++k) all[b->direct_idx[k]] = inf[k];
+          if (fo) {
+            std::vector<double> ee;
+            b->eng.forces(sigma, fo->gamma, fo->force, fo->torque, ee, &b->eng.grad_ok);
+            for (size_t k = 0; k < ee.size(); ++k) en[b->direct_idx[k]] = ee[k];
+          }
+          YQ_HIP(hipStreamSynchronize(b->eng.stream));
         });
     for (int c = 0; c < nconf; ++c) {
       if (info) info[c] = all[c];
       if (!(all[c].residual <= b->prm.tol)) status = YQ_ENOCONV;
     }
+    if (fo && fo->energy)
+      for (int c = 0; c < nconf; ++c) fo->energy[c] = en[c];
   });
   if (rc != YQ_OK) return rc;
   if (status != YQ_OK) b->err = "at least one configuration did not reach the tolerance";
   return status;
+}
+
+}  // namespace
+
+extern "C" {
+
+int yq_batch_solve(yq_batch* b, double* sigma, yq_solve_info* info) {
+  return batch_solve(b, sigma, info, nullptr);
+}
+
+int yq_batch_solve_forces(yq_batch* b, double* sigma, yq_solve_info* info, double gamma,
+                          double* force, double* torque, double* energy) {
+  const ForcesOut fo{gamma, force, torque, energy};
+  return batch_solve(b, sigma, info, &fo);
 }
 
 int yq_batch_forces(yq_batch* b, const double* sigma, double gamma, double* force, double* torque,

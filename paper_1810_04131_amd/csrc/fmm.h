@@ -171,9 +171,12 @@ struct FmmForest {
   // its gradient (FP64 forests), as Fmm::apply_grad of each tree
   void apply_grad(const int* mask, const double* V, const int* col, int64_t T,
                   hipStream_t s) const;
-  // the passes up to the local expansions (gather, P2M, M2M, M2L, L2L)
+  // the passes up to the local expansions (gather, P2M, M2M, M2L, L2L), and the leaf
+  // passes after them: far field (leaves) or its gradient (leaves_grad, FP64 forests)
   void expansions(const int* mask, const double* V, const int* col, int64_t T,
                   hipStream_t s) const;
+  void leaves(const int* mask, hipStream_t s) const;
+  void leaves_grad(const int* mask, hipStream_t s) const;
 };
 
 }  // namespace yq

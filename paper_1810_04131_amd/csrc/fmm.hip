@@ -1695,6 +1695,10 @@ void FmmForest::build(const std::vector<Tree>& trees, bool p2p32, hipStream_t s)
 void FmmForest::apply(const int* mask, const double* V, const int* col, int64_t T,
                       hipStream_t s) const {
   expansions(mask, V, col, T, s);
+  leaves(mask, s);
+}
+
+void FmmForest::leaves(const int* mask, hipStream_t s) const {
   if (nmem == 0) return;
   const int use_col = p <= kColMaxOrder;
   if (n_leaf2) {
@@ -1711,8 +1715,12 @@ void FmmForest::apply(const int* mask, const double* V, const int* col, int64_t 
 
 void FmmForest::apply_grad(const int* mask, const double* V, const int* col, int64_t T,
                            hipStream_t s) const {
-  YQ_REQUIRE(!f32, YQ_EINVAL, "FMM forest: the gradient is FP64");
   expansions(mask, V, col, T, s);
+  leaves_grad(mask, s);
+}
+
+void FmmForest::leaves_grad(const int* mask, hipStream_t s) const {
+  YQ_REQUIRE(!f32, YQ_EINVAL, "FMM forest: the gradient is FP64");
   if (nmem == 0) return;
   const int use_col = p <= kColMaxOrder;
   const int nl = n_leaf2 + n_leaf4;

@@ -314,6 +314,29 @@ def test_batch_graph_replay_equals_eager_with_fmm_configurations(in_engine):
         assert [i["iterations"] for i in ig] == [i["iterations"] for i in ie]
 
 
+@pytest.mark.parametrize("in_engine,precision", [(True, 1), (False, 1), (True, 0)])
+def test_batch_solve_forces_matches_solve_then_forces(in_engine, precision):
+    # the mixed solves' last FP64 residual also gives the forces' gradient far field
+    torch = _torch()
+    cfgs = _forest_configs()
+    prm = dict(panels_per_particle=P, qbx_order=ORDER, tol=1e-9 if precision else 1e-11,
+               precision=precision)
+    a = _lane_batch(cfgs, True, in_engine, **prm)
+    a.set_boundary_data(a.boundary_label())
+    sa, ia = a.solve()
+    Fa, Ta, Ea = a.forces(sa, gamma=1.3)
+    f = _lane_batch(cfgs, True, in_engine, **prm)
+    f.set_boundary_data(f.boundary_label())
+    sf, inf_, Ff, Tf, Ef = f.solve_forces(gamma=1.3)
+    assert [i["iterations"] for i in inf_] == [i["iterations"] for i in ia]
+    assert max(i["residual"] for i in inf_) <= prm["tol"]
+    assert _rel(_np(sf), _np(sa)) < 1e-13
+    sc = max(np.abs(_np(Fa)).max(), np.abs(_np(Ta)).max())
+    assert np.abs(_np(Ff) - _np(Fa)).max() < 1e-12 * sc
+    assert np.abs(_np(Tf) - _np(Ta)).max() < 1e-12 * sc
+    assert np.abs(Ef - Ea).max() < 1e-12 * np.abs(Ea).max()
+
+
 def test_batch_raw_abi_without_device_sync_between_calls():
     # The batch calls are synchronous by contract: driven through the C ABI alone,
     # with no device-wide synchronisation between set-up, boundary data and solve,
