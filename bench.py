@@ -147,6 +147,10 @@ def parse():
                          "threads beside the engine; fused = every configuration in the fused "
                          "direct engine; engine = only the configurations below "
                          "--fmm-min-nodes (the direct members of the hybrid run)")
+    ap.add_argument("--far32", choices=["symmetric", "directed"], default="symmetric",
+                    help="batch: inner far field of the direct members with one kernel "
+                         "evaluation per unordered pair (bsym32_kernel) or per directed pair "
+                         "(bfar32_kernel)")
     ap.add_argument("--fmm-min-nodes", type=int, default=20000,
                     help="serve: requests of at least this many nodes take the FMM lane")
     ap.add_argument("--fp64-requests", type=int, default=None,
@@ -185,16 +189,18 @@ def counters(key):
         return None
 
 
-BATCH_COUNTERS_FILE = "profiles/bfar32_kernel_batch_engine_counters.txt"
+BATCH_COUNTERS_FILE = {"symmetric": "profiles/bsym32_kernel_batch_engine_counters.txt",
+                       "directed": "profiles/bfar32_kernel_batch_engine_counters.txt"}
 BATCH_SRC = ["paper_1810_04131_amd/csrc/batch.hip", "paper_1810_04131_amd/csrc/farfield_core.h",
              "paper_1810_04131_amd/csrc/bessel.h", "paper_1810_04131_amd/csrc/bessel_tables.h"]
 
 
-def batch_counters():
-    """Per-pair HBM bytes and VALU figures of bfar32_kernel from the committed counter
-    summary, or {} when the kernel's source has changed since the counters were taken."""
+def batch_counters(kind):
+    """Per-pair HBM bytes and VALU figures of the batch engine's FP32 far-field kernel
+    (kind: symmetric or directed) from the committed counter summary, or {} when the
+    kernel's source has changed since the counters were taken."""
     import hashlib
-    path = os.path.join(ROOT, BATCH_COUNTERS_FILE)
+    path = os.path.join(ROOT, BATCH_COUNTERS_FILE[kind])
     if not os.path.exists(path):
         return {}
     h = hashlib.sha256()
@@ -404,6 +410,7 @@ def bench_batch(args):
     prm = yq.default_params(panels_per_particle=32, qbx_order=10, tol=tol,
                             precision=yq.YQ_MIXED, restart=60, maxiter=300)
     b = yq.Batch(prm)
+    b.set_symmetric_far(args.far32 == "symmetric")
     if hybrid:
         b.set_fmm(thr, workers=args.fmm_workers, in_engine=forest)
     t0 = time.perf_counter()
@@ -490,11 +497,14 @@ def bench_batch(args):
         err["torque"] = max(err["torque"], float(np.abs(T[poff[c]:poff[c + 1]] - T64).max()
                                                  / np.abs(T64).max()))
     t_step = percentile(lat, 0.5)
-    # roofline of the fused FP32 far-field kernel: algorithmic flops = 40 per
-    # source-target pair (the design's count for the FP32 kernel evaluation);
-    # pairs = what the timed launches evaluated (configurations still iterating)
-    F32_ALG, F64_ALG = 40.0, 50.0
-    bc = batch_counters()
+    # roofline of the fused FP32 far-field kernel: algorithmic flops = 40 per directed
+    # source-target pair (35 for K1(z)/z with the pair's geometry, 5 for the directional
+    # dot product and the accumulation); the symmetric kernel evaluates K1(z)/z once per
+    # unordered pair: (35 + 2 x 5) / 2 = 22.5 per directed pair.  pairs = the directed
+    # pairs the timed launches covered (configurations still iterating)
+    sym = args.far32 == "symmetric"
+    F32_ALG, F64_ALG = (22.5 if sym else 40.0), 50.0
+    bc = batch_counters(args.far32)
     avg32 = ms32 / max(n32, 1)
     achieved = F32_ALG * pairs32 / (ms32 * 1e-3) if ms32 > 0 else 0.0
     out = {
@@ -538,7 +548,8 @@ def bench_batch(args):
                                "all_configs_one_after_another_ms": t_one * 1e3},
         "errors_vs_fp64_path": dict(err, configs=len(ref_idx), reference="FP64 solve to 1e-12"),
         "errors_vs_oracle": errors_vs_oracle_c2(yq, tol),
-        "roofline": {"bound": "alu", "kernel": "bfar32_kernel", "achieved": achieved / 1e12,
+        "roofline": {"bound": "alu", "kernel": "bsym32_kernel" if sym else "bfar32_kernel",
+                     "achieved": achieved / 1e12,
                      "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32,
                      "traffic": (bc["hbm_bytes_per_pair"] * pairs32 / max(n32, 1)
                                  if "hbm_bytes_per_pair" in bc else None),

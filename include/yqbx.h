@@ -361,6 +361,16 @@ int yq_batch_set_fmm(yq_batch* batch, int64_t min_nodes, int32_t workers);
  * yq_batch_set_configs (YQ_ESTATE after). */
 int yq_batch_set_fmm_engine(yq_batch* batch, int32_t enable);
 
+/* Inner (FP32) far field of the direct members.  enable != 0 (default): one
+ * evaluation of K1(z)/z per unordered node pair serves both directions of the
+ * double-layer sum (section 4, eq. double-layer-def: K1(z)/z depends on the
+ * distance only, the factor (x - y).nu on the direction), chunk pairs of 1,024
+ * nodes per work item; 0: one
+ * evaluation per directed pair (target blocks x source chunks).  Both sum the
+ * same pairs in FP32 with the same kernel fits; their rounding differs.  Before
+ * yq_batch_set_configs (YQ_ESTATE after). */
+int yq_batch_set_symmetric_far(yq_batch* batch, int32_t enable);
+
 /* nparticles: host [nconf]; center_xy, angle, semi_axes: host, all configurations'
  * particles concatenated in order (layout as yq_set_particles); kappa: host [nconf].
  * YQ_EGEOM / YQ_EINVAL name the first failing configuration in the message. */

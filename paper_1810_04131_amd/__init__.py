@@ -283,6 +283,12 @@ class Batch:
         self._check(self.lib.yq_batch_set_fmm_engine(self.h, int(bool(in_engine))))
         return self
 
+    def set_symmetric_far(self, enable=True):
+        """Inner far field: one evaluation per unordered pair (default) or per directed
+        pair (before set_configs)."""
+        self._check(self.lib.yq_batch_set_symmetric_far(self.h, int(bool(enable))))
+        return self
+
     def _f64(self, *shape):
         return self.torch.empty(*shape, dtype=self.torch.float64, device=self.device)
 

@@ -8,6 +8,8 @@
 
 namespace yq {
 
+constexpr int SC = 1024;   // nodes per chunk of the symmetric FP32 far field (bsym32)
+
 // What the fused kernels need of one configuration (device copy, one per config).
 struct ConfDev {
   const double* x;
@@ -29,6 +31,7 @@ struct ConfDev {
   double kap2;
   int P, win;
   int tblocks, chunks, chunk;
+  int chunks32;   // FP32 partial slots: chunks (bfar32) or ceil(N / SC) (bsym32)
   int kb;         // Krylov reduction blocks
   int64_t kpoff;  // offset of its multi-dot partials
   int fmm;        // far field from the FMM forest (part64, one chunk), not the fused sums
@@ -65,6 +68,10 @@ struct Engine {
   DevBuf<double> tab64;       // FP64 Bessel coefficients (shared by all configurations)
   DevBuf<ConfDev> conf;
   DevBuf<int4> items;
+  // symmetric FP32 far field: (configuration, chunk p, chunk q >= p) items
+  bool sym32 = true;
+  DevBuf<int4> sitems;
+  int nsitems = 0;
   DevBuf<int2> kblk;
   DevBuf<int> node_conf;
   int nitems = 0, nkblk = 0;
@@ -90,7 +97,7 @@ struct Engine {
   ~Engine();
   void init(const yq_params& p);
   void rebuild();
-  int grid_blocks() const;
+  int grid_blocks(int n) const;   // persistent blocks for n work items
   void matvec(int prec, const int* mask, const double* Vin, const int* col, double* out);
   void matvec_part(int part, int prec, const int* mask, const double* Vin, const int* col,
                    double* out);

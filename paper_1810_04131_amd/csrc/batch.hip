@@ -103,10 +103,13 @@ __global__ __launch_bounds__(BB) void bfar64_kernel(const ConfDev* __restrict__ 
   }
 }
 
-// Packs the FP32 source records of every active configuration.
+// Packs the FP32 source records of every active configuration: positions relative
+// to the node's 256-node tile centre (bfar32) or, with sym set, to its 64-node
+// group centre (bsym32), scaled by kappa log2(e).
 __global__ void bpack32_kernel(const ConfDev* __restrict__ cf, const int* __restrict__ node_conf,
                                int64_t T, const int* __restrict__ mask,
-                               const double* __restrict__ V, const int* __restrict__ col) {
+                               const double* __restrict__ V, const int* __restrict__ col,
+                               int sym) {
   const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (g >= T) return;
   const int c = node_conf[g];
@@ -115,7 +118,13 @@ __global__ void bpack32_kernel(const ConfDev* __restrict__ cf, const int* __rest
   if (cd.fmm) return;   // no FP32 source records: its far field comes from the forest
   const int64_t i = g - cd.off;
   const double sc = V[(col ? (int64_t)col[c] * T : 0) + g] * cd.f32.qc;
-  const float2 r = cd.rel[i];
+  float2 r;
+  if (sym) {
+    const double4 gc = cd.f32.grp[i / FG];
+    r = make_float2((float)((cd.x[i] - gc.x) * cd.f32.s), (float)((cd.y[i] - gc.y) * cd.f32.s));
+  } else {
+    r = cd.rel[i];
+  }
   const_cast<float4*>(cd.f32.src)[i] =
       make_float4(r.x, r.y, (float)(cd.wnx[i] * sc), (float)(cd.wny[i] * sc));
 }
@@ -143,6 +152,175 @@ __global__ __launch_bounds__(BB) void bfar32_kernel(const ConfDev* __restrict__ 
   }
 }
 
+// ---- symmetric FP32 far field ------------------------------------------------------------
+//
+// K1(z)/z depends on the pair only through |x_i - x_j|, so one evaluation serves both
+// directions: target i gains K (x_i - x_j).q_j and target j gains -K (x_i - x_j).q_i.
+// Work items are pairs p <= q of node chunks (SC nodes) of one configuration, so a
+// configuration's items depend only on its size.  Each wavefront of a block takes
+// groups of chunk p (64 nodes, one per lane) and visits the groups of chunk q (for p = q
+// those at or after its own):
+//   far pair of groups (kappa x the gap between their circles >= 2): one evaluation per
+//     unordered pair.  The other group's records are staged in LDS twice over so that
+//     lane l reads record (l + k) mod 64 at step k through one address and an immediate
+//     offset; the reverse partial sum moves with its node by a one-lane rotation of the
+//     wavefront per step, so that after 64 steps lane l holds the sum of node l;
+//   close pair: bfar32's panel-classified one-directional sums, in both directions;
+//   a group with itself: the forward sums only.
+// Reverse sums go to a per-wavefront LDS row and are added in a fixed order: the
+// result does not depend on timing.  Output: the sums of targets of chunk t over the
+// sources of chunk u go to part32[u * N + i] (bfinish adds ceil(N / SC) slots).
+constexpr int SW = BB / FG;         // wavefronts per block
+static_assert(SW == 4 && SC % FG == 0, "four wavefronts; chunks of whole groups");
+constexpr float FAR_AWAY = 1e18f;   // position of padding records (their strength is 0)
+
+__device__ __forceinline__ float rotl1(float v) {   // lane l <- lane (l + 1) mod 64
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x134,
+                                                            0xF, 0xF, true));
+}
+
+// Orders this wavefront's LDS accesses on either side (LDS executes a wavefront's
+// accesses in issue order; this keeps the compiler from moving them across).
+__device__ __forceinline__ void wave_lds_order() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// One far pair of groups: the lane's node (tx, ty relative to the other group's centre,
+// scaled; strength (qx, qy)) against the 64 staged records st[k] = record (lane + k) mod 64.
+template <int NH, const float (&H)[NH]>
+__device__ __forceinline__ void sym_far_block(float tx, float ty, float qx, float qy,
+                                              const float4* st, float& facc, float& racc) {
+#pragma unroll 16
+  for (int k = 0; k < FG; ++k) {
+    const float4 b = st[k];
+    const float dx = tx - b.x, dy = ty - b.y;
+    const float z2 = fmaf(dx, dx, dy * dy);
+    const float yv = __builtin_amdgcn_rsqf(z2);
+    const float z = z2 * yv;
+    const float e = __builtin_amdgcn_exp2f(fmaf(-1.5f, __builtin_amdgcn_logf(z), -z));
+    const float eh = e * horner(H, yv);
+    facc = fmaf(eh, fmaf(dx, b.z, dy * b.w), facc);
+    racc = rotl1(racc - eh * fmaf(dx, qx, dy * qy));
+  }
+}
+
+// One-directional sums over the sources [s0, s0 + ns) of one group (ns a multiple of
+// 16) for a target at (xt, yt) of a group with circle (gx, gy, gr); (tx, ty) is the
+// target relative to the source group's centre, scaled.  Each panel takes the class
+// of its own circle, as in far32_range.
+__device__ __forceinline__ void sym_panels(const ConfDev& cd, double xt, double yt, float tx,
+                                           float ty, double gx, double gy, double gr, int64_t s0,
+                                           int ns, float& accf, float& accn) {
+  kptr<float> src = as_k((const float*)cd.f32.src);
+  for (int64_t js = s0; js < s0 + ns; js += Q) {
+    kptr<double> pc = as_k((const double*)cd.f32.pan) + 4 * (js / Q);
+    const double px = gx - pc[0], py = gy - pc[1];
+    const double z = cd.kappa * (sqrt(px * px + py * py) - gr - pc[2]);
+    kptr<float> sp = src + 4 * js;
+    if (z >= 8.0)
+      accf = far32_far_tile<4, kH1Y_32_z8>(tx, ty, sp, Q, accf);
+    else if (z >= 4.0)
+      accf = far32_far_tile<5, kH1Y_32_z4>(tx, ty, sp, Q, accf);
+    else if (z >= 2.0)
+      accf = far32_far_tile<7, kH1Y_32>(tx, ty, sp, Q, accf);
+    else
+      accn = far32_near_tile(xt, yt, as_k(cd.x) + js, as_k(cd.y) + js, sp, Q, cd.f32.kap2, accn);
+  }
+}
+
+__global__ __launch_bounds__(BB) void bsym32_kernel(const ConfDev* __restrict__ cf,
+                                                    const int4* __restrict__ items, int nitems,
+                                                    const int* __restrict__ mask,
+                                                    unsigned long long* __restrict__ pairs) {
+  __shared__ float rev[SW][SC];
+  __shared__ float4 stage[SW][2 * FG];
+  const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / FG));
+  const int lane = (int)(threadIdx.x % FG);
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const int4 w = items[it];
+    const int c = w.x;
+    if (!mask[c]) continue;
+    const ConfDev& cd = cf[c];
+    const int64_t N = cd.N;
+    const int p = w.y, q = w.z;
+    const int64_t a0 = (int64_t)p * SC, b0 = (int64_t)q * SC;
+    const int na = (int)min((int64_t)SC, N - a0);
+    const int nb = (int)min((int64_t)SC, N - b0);
+    if (pairs && threadIdx.x == 0)
+      atomicAdd(pairs, (unsigned long long)(p == q ? (int64_t)na * na : 2 * (int64_t)na * nb));
+    const int nga = (na + FG - 1) / FG, ngb = (nb + FG - 1) / FG;
+    for (int t = lane; t < SC; t += FG) rev[wv][t] = 0.0f;
+    kptr<double> grp = as_k((const double*)cd.f32.grp);
+    const float4* src = cd.f32.src;
+    const double s = cd.f32.s, kappa = cd.kappa;
+    const float nscale = cd.f32.nscale;
+    // groups of chunk p in snake order over the wavefronts (balances the triangle of p = q)
+    for (int r = 0; SW * r < nga; ++r) {
+      const int a = SW * r + ((r & 1) ? SW - 1 - wv : wv);
+      if (a >= nga) continue;
+      const int64_t ga = a0 / FG + a;
+      const int64_t ia = ga * FG + lane;
+      const bool va = ia < N;
+      const int nav = (int)min((int64_t)FG, N - ga * FG);
+      const float4 ra = va ? src[ia] : make_float4(FAR_AWAY, FAR_AWAY, 0.0f, 0.0f);
+      const double xa = va ? cd.x[ia] : 0.0, ya = va ? cd.y[ia] : 0.0;
+      const double cax = grp[4 * ga], cay = grp[4 * ga + 1], car = grp[4 * ga + 2];
+      float ff = 0.0f, fn = 0.0f;
+      for (int b = (p == q ? a : 0); b < ngb; ++b) {
+        const int64_t gb = b0 / FG + b;
+        const int64_t jb = gb * FG;
+        const int nbv = (int)min((int64_t)FG, N - jb);
+        if (p == q && b == a) {
+          sym_panels(cd, xa, ya, ra.x, ra.y, cax, cay, car, jb, nbv, ff, fn);
+          continue;
+        }
+        const double cbx = grp[4 * gb], cby = grp[4 * gb + 1], cbr = grp[4 * gb + 2];
+        const double ox = cax - cbx, oy = cay - cby;
+        const double z = kappa * (sqrt(ox * ox + oy * oy) - car - cbr);
+        const float offx = (float)(ox * s), offy = (float)(oy * s);
+        const float4 rb =
+            lane < nbv ? src[jb + lane] : make_float4(-FAR_AWAY, -FAR_AWAY, 0.0f, 0.0f);
+        float racc = 0.0f;
+        if (z >= 2.0) {
+          wave_lds_order();
+          stage[wv][lane] = rb;
+          stage[wv][lane + FG] = rb;
+          wave_lds_order();
+          const float tx = ra.x + offx, ty = ra.y + offy;
+          const float4* st = &stage[wv][lane];
+          if (z >= 8.0)
+            sym_far_block<4, kH1Y_32_z8>(tx, ty, ra.z, ra.w, st, ff, racc);
+          else if (z >= 4.0)
+            sym_far_block<5, kH1Y_32_z4>(tx, ty, ra.z, ra.w, st, ff, racc);
+          else
+            sym_far_block<7, kH1Y_32>(tx, ty, ra.z, ra.w, st, ff, racc);
+        } else {
+          sym_panels(cd, xa, ya, ra.x + offx, ra.y + offy, cax, cay, car, jb, nbv, ff, fn);
+          const double xb = lane < nbv ? cd.x[jb + lane] : 0.0;
+          const double yb = lane < nbv ? cd.y[jb + lane] : 0.0;
+          float rf = 0.0f, rn = 0.0f;
+          sym_panels(cd, xb, yb, rb.x - offx, rb.y - offy, cbx, cby, cbr, ga * FG, nav, rf, rn);
+          racc = fmaf(rn, nscale, rf);
+        }
+        rev[wv][b * FG + lane] += racc;
+      }
+      const float fwd = fmaf(fn, nscale, ff);
+      if (p == q)
+        rev[wv][a * FG + lane] += fwd;
+      else if (va)
+        cd.part32[(int64_t)q * N + ia] = fwd;
+    }
+    __syncthreads();
+    const int64_t o0 = p == q ? a0 : b0;
+    const int no = p == q ? na : nb;
+    for (int t = threadIdx.x; t < no; t += BB)
+      cd.part32[(int64_t)p * N + o0 + t] = ((rev[0][t] + rev[1][t]) + rev[2][t]) + rev[3][t];
+    __syncthreads();
+  }
+}
+
 // out[g] = (kappa^2/2pi) sum_chunks partial + correction, for every node of an active config.
 __global__ void bfinish_kernel(const ConfDev* __restrict__ cf, const int* __restrict__ node_conf,
                                int64_t T, const int* __restrict__ mask, int f32,
@@ -160,7 +338,7 @@ __global__ void bfinish_kernel(const ConfDev* __restrict__ cf, const int* __rest
   if (!f32 || cd.fmm) {
     for (int k = 0; k < cd.chunks; ++k) s += cd.part64[(int64_t)k * N + i];
   } else {
-    for (int k = 0; k < cd.chunks; ++k) s += (double)cd.part32[(int64_t)k * N + i];
+    for (int k = 0; k < cd.chunks32; ++k) s += (double)cd.part32[(int64_t)k * N + i];
   }
   s *= cd.kappa * cd.kappa / (2.0 * PI);
   const double corr = correction_row(i, N, cd.P, cd.win, cd.W, cd.xrow, cd.xpan, cd.xvals, sg);
@@ -586,7 +764,7 @@ void Engine::init(const yq_params& p) {
 void Engine::rebuild() {
   const int nc = (int)members.size();
   std::vector<ConfDev> h(nc);
-  std::vector<int4> it;
+  std::vector<int4> it, sit;
   std::vector<int2> kb;
   std::vector<FmmForest::Tree> tin, thi;
   std::vector<int2> fi;
@@ -636,6 +814,14 @@ void Engine::rebuild() {
         pb->gpartial.reserve((size_t)d.chunks * 2 * pb->N);
         for (int t = 0; t < d.tblocks; ++t)
           for (int s = 0; s < d.chunks; ++s) it.push_back(make_int4(c, t, s, 0));
+        d.chunks32 = d.chunks;
+        if (sym32) {
+          d.chunks32 = (int)((pb->N + SC - 1) / SC);
+          pb->partial32.reserve((size_t)d.chunks32 * pb->N);
+          d.part32 = pb->partial32.p;
+          for (int p = 0; p < d.chunks32; ++p)
+            for (int q = p; q < d.chunks32; ++q) sit.push_back(make_int4(c, p, q, 0));
+        }
       }
       for (int b = 0; b < d.kb; ++b) kb.push_back(make_int2(c, b));
       d.nx = pb->nx.p;
@@ -654,6 +840,20 @@ void Engine::rebuild() {
   }
   nitems = (int)it.size();
   nkblk = (int)kb.size();
+  // symmetric items by decreasing pair count (the persistent grid deals them in order;
+  // each item's sums do not depend on the order)
+  auto spairs = [&](const int4& v) {
+    const int64_t N = h[v.x].N;
+    const int64_t na = std::min<int64_t>(SC, N - (int64_t)v.y * SC);
+    const int64_t nb = std::min<int64_t>(SC, N - (int64_t)v.z * SC);
+    return v.y == v.z ? na * na : 2 * na * nb;
+  };
+  std::stable_sort(sit.begin(), sit.end(),
+                   [&](const int4& u, const int4& v) { return spairs(u) > spairs(v); });
+  nsitems = (int)sit.size();
+  sitems.alloc(std::max(nsitems, 1));
+  if (nsitems)
+    YQ_HIP(hipMemcpyAsync(sitems.p, sit.data(), nsitems * sizeof(int4), hipMemcpyHostToDevice, stream));
   nfitems = (int)fi.size();
   fitems.alloc(std::max(nfitems, 1));
   if (nfitems)
@@ -717,9 +917,9 @@ void Engine::rebuild() {
   YQ_HIP(hipStreamSynchronize(stream));
 }
 
-int Engine::grid_blocks() const {
+int Engine::grid_blocks(int n) const {
   const int want = persist_blocks > 0 ? persist_blocks : 2048;
-  return std::max(1, std::min(nitems, want));
+  return std::max(1, std::min(n, want));
 }
 
 // The three parts of out = A sigma (precision prec) for configurations in mask,
@@ -731,15 +931,18 @@ void Engine::matvec_part(int part, int prec, const int* mask, const double* Vin,
   unsigned long long* pc = prof_on ? prof_pairs.p + (prec == YQ_MIXED ? 1 : 0) : nullptr;
   if (part == 0) {
     if (prec == YQ_MIXED && nitems > 0)
-      bpack32_kernel<<<nb256(T), 256, 0, stream>>>(conf.p, node_conf.p, T, mask, Vin, col);
+      bpack32_kernel<<<nb256(T), 256, 0, stream>>>(conf.p, node_conf.p, T, mask, Vin, col,
+                                                   sym32 ? 1 : 0);
     // the FMM members' far field (inner operator, or the FP64 residual operator)
     (prec == YQ_MIXED ? forest_in : forest_hi).apply(mask, Vin, col, T, stream);
   } else if (part == 1) {
     if (nitems == 0) return;
-    if (prec == YQ_MIXED)
-      bfar32_kernel<<<grid_blocks(), BB, 0, stream>>>(conf.p, items.p, nitems, mask, pc);
+    if (prec == YQ_MIXED && sym32)
+      bsym32_kernel<<<grid_blocks(nsitems), BB, 0, stream>>>(conf.p, sitems.p, nsitems, mask, pc);
+    else if (prec == YQ_MIXED)
+      bfar32_kernel<<<grid_blocks(nitems), BB, 0, stream>>>(conf.p, items.p, nitems, mask, pc);
     else
-      bfar64_kernel<<<grid_blocks(), BB, 0, stream>>>(conf.p, items.p, nitems, mask, Vin, col, T,
+      bfar64_kernel<<<grid_blocks(nitems), BB, 0, stream>>>(conf.p, items.p, nitems, mask, Vin, col, T,
                                                       tab64.p, pc);
   } else {
     bfinish_kernel<<<nb256(T), 256, 0, stream>>>(conf.p, node_conf.p, T, mask, prec == YQ_MIXED,
@@ -1094,7 +1297,7 @@ void Engine::forces(const double* sigma, double gamma, double* force, double* to
   if (nneed) {   // gradient far field of the members whose solve did not leave it
     upload_mask(pmask, need);
     if (nitems)
-      bgrad64_kernel<<<grid_blocks(), BB, 0, stream>>>(conf.p, items.p, nitems, pmask.p, sigma,
+      bgrad64_kernel<<<grid_blocks(nitems), BB, 0, stream>>>(conf.p, items.p, nitems, pmask.p, sigma,
                                                        tab64.p);
     forest_hi.apply_grad(pmask.p, sigma, nullptr, T, stream);
   }
@@ -1143,14 +1346,14 @@ void Engine::resid(const std::vector<int>& plain, const std::vector<int>& fused,
     unsigned long long* pc = prof_on ? prof_pairs.p : nullptr;
     hipEvent_t a = prof_on ? prof_event() : nullptr;
     if (a) YQ_HIP(hipEventRecord(a, stream));
-    bfar64_kernel<<<grid_blocks(), BB, 0, stream>>>(conf.p, items.p, nitems, pmask.p, x, nullptr, T,
+    bfar64_kernel<<<grid_blocks(nitems), BB, 0, stream>>>(conf.p, items.p, nitems, pmask.p, x, nullptr, T,
                                                     tab64.p, pc);
     if (a) {
       hipEvent_t b = prof_event();
       YQ_HIP(hipEventRecord(b, stream));
       prof_ev[0].push_back({a, b});
     }
-    bfused64_kernel<<<grid_blocks(), BB, 0, stream>>>(conf.p, items.p, nitems, fmask.p, x, nullptr,
+    bfused64_kernel<<<grid_blocks(nitems), BB, 0, stream>>>(conf.p, items.p, nitems, fmask.p, x, nullptr,
                                                       T, tab64.p);
   }
   bfinish_kernel<<<nb256(T), 256, 0, stream>>>(conf.p, node_conf.p, T, inc.p, 0, x, nullptr, out);

@@ -404,6 +404,14 @@ int yq_batch_set_fmm_engine(yq_batch* b, int32_t enable) {
   });
 }
 
+int yq_batch_set_symmetric_far(yq_batch* b, int32_t enable) {
+  return bguard(b, [&] {
+    YQ_REQUIRE(b, YQ_EINVAL, "null batch");
+    YQ_REQUIRE(!b->ready, YQ_ESTATE, "the far-field kernel is set before yq_batch_set_configs");
+    b->eng.sym32 = enable != 0;
+  });
+}
+
 int yq_batch_profile_enable(yq_batch* b, int32_t enable) {
   return bguard(b, [&] {
     YQ_REQUIRE(b, YQ_EINVAL, "null batch");

@@ -405,3 +405,67 @@ def test_batch_far_field_timers_count_pairs_and_leave_results_unchanged():
     # every evaluated pair belongs to a configuration's own N^2 block
     assert 0 < pairs <= float((N * N * np.array([i["matvecs_fp32"] + 2 for i in infos])).sum())
     assert fp32_matvecs > 0
+
+
+def _sym_configs():
+    # 2 chunks of 1,024 nodes at 12 panels (1,728 nodes); at 13 panels the 1,456 nodes
+    # end in a ragged group of 48; one single-chunk configuration
+    return [
+        workloads.random_ellipses(9, 16.0, 0.9, seed=4),
+        workloads.random_ellipses(7, 14.0, 1.1, seed=5),
+        workloads.random_ellipses(3, 9.0, 0.7, seed=1),
+    ]
+
+
+@pytest.mark.parametrize("panels", [12, 13])
+def test_batch_symmetric_far_field_matches_directed_and_oracle(panels):
+    """One kernel evaluation per unordered pair (default) against one per directed pair
+    and against the oracle's operator; the symmetric items of a configuration alone
+    give the same bits as in the mix, and the timers count every directed pair."""
+    torch = _torch()
+    cfgs = _sym_configs()
+    prm = yq.default_params(panels_per_particle=panels, qbx_order=ORDER)
+    sym = yq.Batch(prm)
+    sym.set_configs(cfgs)
+    dirb = yq.Batch(prm).set_symmetric_far(False)
+    dirb.set_configs(cfgs)
+    assert np.array_equal(sym.offsets, dirb.offsets)
+    N = np.diff(sym.offsets)
+    assert N.max() > 1024 and (N % 64 != 0).any() == (panels == 13)
+    sig = np.concatenate([workloads.random_density(int(n), 11 + c) for c, n in enumerate(N)])
+    sym.profile(True)
+    o_sym = _np(sym.apply_operator(sig, yq.YQ_MIXED))
+    n, ms, pairs = sym.profile_read(yq.YQ_MIXED)
+    assert n == 1 and ms > 0.0 and pairs == float((N * N).sum())
+    o_dir = _np(dirb.apply_operator(sig, yq.YQ_MIXED))
+    o_64 = _np(sym.apply_operator(sig))
+    # the oracle's operator on one two-chunk configuration (ragged at 13 panels); the
+    # FP64 engine operator, which matches the oracle to 1e-12, on all of them
+    oc = 0 if panels == 12 else 1
+    so = slice(int(sym.offsets[oc]), int(sym.offsets[oc + 1]))
+    ref = oracle.build_matrices(oracle.discretize(cfgs[oc], Params(panels=panels,
+                                                                   qbx_order=ORDER))) @ sig[so]
+    assert _rel(o_64[so], ref) < 1e-12
+    assert _rel(o_sym[so], ref) < 5e-6 and _rel(o_dir[so], ref) < 5e-6
+    for c, cfg in enumerate(cfgs):
+        s = slice(int(sym.offsets[c]), int(sym.offsets[c + 1]))
+        ref = o_64[s]
+        assert _rel(o_sym[s], ref) < 5e-6, c
+        assert _rel(o_dir[s], ref) < 5e-6, c
+        assert _rel(o_sym[s], o_dir[s]) < 5e-6, c
+        alone = yq.Batch(prm)
+        alone.set_configs([cfg])
+        assert np.array_equal(_np(alone.apply_operator(sig[s], yq.YQ_MIXED)), o_sym[s]), c
+    # the mixed solve with the symmetric inner operator reaches the FP64 tolerance
+    sb = yq.Batch(yq.default_params(panels_per_particle=panels, qbx_order=ORDER, tol=1e-10,
+                                    precision=1))
+    sb.set_configs(cfgs)
+    sb.set_boundary_data(sb.boundary_label())
+    ss, infos = sb.solve()
+    fb = yq.Batch(yq.default_params(panels_per_particle=panels, qbx_order=ORDER, tol=1e-12))
+    fb.set_configs(cfgs)
+    fb.set_boundary_data(fb.boundary_label())
+    sf, _ = fb.solve()
+    assert all(i["residual"] <= 1e-10 for i in infos)
+    assert _rel(_np(ss), _np(sf)) < 1e-8
+    torch.cuda.synchronize()
