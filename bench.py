@@ -151,8 +151,12 @@ def parse():
                     help="batch: inner far field of the direct members with one kernel "
                          "evaluation per unordered pair (bsym32_kernel) or per directed pair "
                          "(bfar32_kernel)")
-    ap.add_argument("--fmm-min-nodes", type=int, default=20000,
-                    help="serve: requests of at least this many nodes take the FMM lane")
+    ap.add_argument("--fmm-min-nodes", type=int, default=None,
+                    help="batch: configurations of at least this many nodes take the FMM "
+                         "(default 0 for hybrid: every configuration is a tree of the forest, "
+                         "measured fastest at every size of the workload; 20000 for lane and "
+                         "engine); serve: requests of at least this many nodes take the FMM "
+                         "lane (default 20000)")
     ap.add_argument("--fp64-requests", type=int, default=None,
                     help="serve: requests of the trace (from the start) replayed on the FP64 "
                          "one-at-a-time path (default all)")
@@ -189,6 +193,10 @@ def counters(key):
         return None
 
 
+# the single-problem path's own crossover from the direct far field to the FMM (the
+# library's automatic choice): the one-at-a-time baselines use it
+SINGLE_FMM_NODES = 20000
+
 BATCH_COUNTERS_FILE = {"symmetric": "profiles/bsym32_kernel_batch_engine_counters.txt",
                        "directed": "profiles/bfar32_kernel_batch_engine_counters.txt"}
 BATCH_SRC = ["paper_1810_04131_amd/csrc/batch.hip", "paper_1810_04131_amd/csrc/farfield_core.h",
@@ -199,12 +207,27 @@ def batch_counters(kind):
     """Per-pair HBM bytes and VALU figures of the batch engine's FP32 far-field kernel
     (kind: symmetric or directed) from the committed counter summary, or {} when the
     kernel's source has changed since the counters were taken."""
+    return _kv_counters(BATCH_COUNTERS_FILE[kind], BATCH_SRC)
+
+
+LEAF_COUNTERS_FILE = "profiles/forest_leaf_kernel_batch_counters.txt"
+LEAF_SRC = ["paper_1810_04131_amd/csrc/fmm.hip", "paper_1810_04131_amd/csrc/farfield_core.h",
+            "paper_1810_04131_amd/csrc/bessel.h", "paper_1810_04131_amd/csrc/bessel_tables.h"]
+
+
+def leaf_counters():
+    """Per-pair HBM bytes and VALU figures of the forest's FP32 leaf pass from the
+    committed counter summary, or {} when its source has changed since."""
+    return _kv_counters(LEAF_COUNTERS_FILE, LEAF_SRC)
+
+
+def _kv_counters(path, srcs):
     import hashlib
-    path = os.path.join(ROOT, BATCH_COUNTERS_FILE[kind])
+    path = os.path.join(ROOT, path)
     if not os.path.exists(path):
         return {}
     h = hashlib.sha256()
-    for f in BATCH_SRC:
+    for f in srcs:
         h.update(open(os.path.join(ROOT, f), "rb").read())
     kv = {}
     for line in open(path):
@@ -401,11 +424,14 @@ def bench_batch(args):
     cfgs = batch_layouts(plan)
     log(f"{len(cfgs)} configurations drawn in {time.perf_counter() - t0:.1f} s")
     engine_only = args.batch_lane == "engine"
-    if engine_only:
-        cfgs = [c for c in cfgs if c.n * 512 < args.fmm_min_nodes]
-    hybrid = args.batch_lane in ("hybrid", "lane")
     forest = args.batch_lane == "hybrid"
-    thr = args.fmm_min_nodes if hybrid else None
+    min_nodes = args.fmm_min_nodes
+    if min_nodes is None:
+        min_nodes = 0 if forest else SINGLE_FMM_NODES
+    if engine_only:
+        cfgs = [c for c in cfgs if c.n * 512 < min_nodes]
+    hybrid = args.batch_lane in ("hybrid", "lane")
+    thr = min_nodes if hybrid else None
     tol = args.tol
     prm = yq.default_params(panels_per_particle=32, qbx_order=10, tol=tol,
                             precision=yq.YQ_MIXED, restart=60, maxiter=300)
@@ -431,7 +457,8 @@ def bench_batch(args):
         step()
         log(f"warm-up step {k + 1} done")
     for prec in (yq.YQ_MIXED, yq.YQ_FP64):
-        b.profile_read(prec, reset=True)
+        for kern in ("direct", "leaf"):
+            b.profile_read(prec, reset=True, kernel=kern)
     lat = []
     torch.cuda.synchronize()
     t_all = time.perf_counter()
@@ -444,6 +471,8 @@ def bench_batch(args):
     t_all = time.perf_counter() - t_all
     n32, ms32, pairs32 = b.profile_read(yq.YQ_MIXED)
     n64, ms64, pairs64 = b.profile_read(yq.YQ_FP64)
+    nl32, msl32, pairsl32 = b.profile_read(yq.YQ_MIXED, kernel="leaf")
+    nl64, msl64, pairsl64 = b.profile_read(yq.YQ_FP64, kernel="leaf")
     its = np.array([i["iterations"] for i in infos])
     ref = np.array([i["outer_steps"] for i in infos])
     mv = np.array([i["matvecs_fp32"] + i["matvecs_fp64"] for i in infos], dtype=float)
@@ -468,7 +497,7 @@ def bench_batch(args):
                                  precision=yq.YQ_FP64, restart=60, maxiter=400, **kw)
 
     # FP64 one-at-a-time path: each configuration alone (FP64 solve to the same
-    # tolerance with the direct far field below the lane threshold and the FP64
+    # tolerance with the direct far field below SINGLE_FMM_NODES and the FP64
     # FMM above, then its forces), on every k-th configuration
     stride = max(1, len(cfgs) // max(args.single_baseline, 1))
     sample = list(range(0, len(cfgs), stride))
@@ -476,7 +505,7 @@ def bench_batch(args):
     for k, c in enumerate(sample):
         torch.cuda.synchronize()
         a = time.perf_counter()
-        single(c, p64(tol, lane[c]))
+        single(c, p64(tol, N[c] >= SINGLE_FMM_NODES))
         torch.cuda.synchronize()
         service.append(time.perf_counter() - a)
         if (k + 1) % 64 == 0:
@@ -488,7 +517,7 @@ def bench_batch(args):
     err = {"density": 0.0, "force": 0.0, "torque": 0.0}
     ref_idx = list(range(0, len(cfgs), max(1, len(cfgs) // args.error_configs)))
     for c in ref_idx:
-        s64, F64, T64 = single(c, p64(1e-12, lane[c]))
+        s64, F64, T64 = single(c, p64(1e-12, N[c] >= SINGLE_FMM_NODES))
         s64, F64, T64 = s64.cpu().numpy(), F64.cpu().numpy().reshape(-1, 2), T64.cpu().numpy()
         err["density"] = max(err["density"], float(np.abs(sig[offs[c]:offs[c + 1]] - s64).max()
                                                    / np.abs(s64).max()))
@@ -507,6 +536,50 @@ def bench_batch(args):
     bc = batch_counters(args.far32)
     avg32 = ms32 / max(n32, 1)
     achieved = F32_ALG * pairs32 / (ms32 * 1e-3) if ms32 > 0 else 0.0
+    direct = {"bound": "alu", "kernel": "bsym32_kernel" if sym else "bfar32_kernel",
+              "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
+              "frac": achieved / PEAK_FP32,
+              "traffic": (bc["hbm_bytes_per_pair"] * pairs32 / max(n32, 1)
+                          if "hbm_bytes_per_pair" in bc else None),
+              "flops_per_pair": F32_ALG,
+              "counter_flops_per_pair": bc.get("valu_flops_per_pair"),
+              "counter_frac": (bc["valu_flops_per_pair"] * pairs32 / (ms32 * 1e-3) / PEAK_FP32
+                               if "valu_flops_per_pair" in bc and ms32 > 0 else None),
+              "pairs_per_launch": pairs32 / max(n32, 1), "avg_launch_ms": avg32,
+              "launches": n32, "total_ms": ms32}
+    # the forest's FP32 leaf pass (both launches of an operator application, bracketed
+    # together): 40 flop per directed pair of its direct interactions, the pair's
+    # general FP32 path (every pair of neighbouring leaves takes it); the FP64 local
+    # expansion evaluated at each target in the same launches is not counted
+    lc = leaf_counters()
+    ach_l = 40.0 * pairsl32 / (msl32 * 1e-3) if msl32 > 0 else 0.0
+    leaf = {"bound": "alu", "kernel": "forest_leaf_kernel", "achieved": ach_l / 1e12,
+            "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s", "frac": ach_l / PEAK_FP32,
+            "traffic": (lc["hbm_bytes_per_pair"] * pairsl32 / max(nl32, 1)
+                        if "hbm_bytes_per_pair" in lc else None),
+            "flops_per_pair": 40.0,
+            "counter_flops_per_pair": lc.get("valu_flops_per_pair"),
+            "counter_frac": (lc["valu_flops_per_pair"] * pairsl32 / (msl32 * 1e-3) / PEAK_FP32
+                             if "valu_flops_per_pair" in lc and msl32 > 0 else None),
+            "pairs_per_launch": pairsl32 / max(nl32, 1),
+            "avg_launch_ms": msl32 / max(nl32, 1), "launches": nl32, "total_ms": msl32,
+            "launch_note": "one timed launch = the leaf pass of one operator application "
+                           "(its two launches: leaves served by 2 and by 4 wavefronts)"}
+    fp64 = {"direct_kernel": {"kernel": "bfar64_kernel", "launches": n64,
+                              "avg_launch_ms": ms64 / max(n64, 1),
+                              "achieved": F64_ALG * pairs64 / (ms64 * 1e-3) / 1e12
+                              if ms64 > 0 else None,
+                              "peak": PEAK_FP64 / 1e12,
+                              "frac": F64_ALG * pairs64 / (ms64 * 1e-3) / PEAK_FP64
+                              if ms64 > 0 else None},
+            "forest_leaf": {"kernel": "forest_leaf_kernel (FP64 pairs)", "launches": nl64,
+                            "avg_launch_ms": msl64 / max(nl64, 1),
+                            "pairs_per_launch": pairsl64 / max(nl64, 1)}}
+    # the dominant FP32 kernel of the timed steps carries the roofline
+    if msl32 > ms32:
+        roof = dict(leaf, other_fp32_kernel=direct if n32 and pairs32 else None, fp64=fp64)
+    else:
+        roof = dict(direct, other_fp32_kernel=leaf if nl32 and pairsl32 else None, fp64=fp64)
     out = {
         "metric": "source-target interactions/s per matvec; solves/s + p50/p99 latency at 1e-8 rel err",
         "value": len(cfgs) / t_step, "unit": "solves/s", "n_gpus": 1, "steps": len(lat),
@@ -518,7 +591,11 @@ def bench_batch(args):
                                f"particle, kappa~U[0.5,2], QBX order 10, mixed FP32/FP64 to a "
                                f"relative residual of {tol:g}; one step = batched solve + "
                                f"forces/torques of every configuration; "
-                               + (f"every configuration in the fused engine, one graph-replayed "
+                               + (f"every configuration a tree of the engine's FMM forest (FMM "
+                                  f"order 20 inner / 40 FP64 residuals), one graph-replayed "
+                                  f"iteration for the whole batch; the forces of every "
+                                  f"configuration in one batched pass" if forest and thr == 0
+                                  else f"every configuration in the fused engine, one graph-replayed "
                                   f"iteration for the whole batch: {int((~lane).sum())} below "
                                   f"{thr} nodes with the fused direct far field, {int(lane.sum())} "
                                   f"from {thr} nodes on as trees of the FMM forest (FMM order 20 "
@@ -530,7 +607,7 @@ def bench_batch(args):
                                   f"({args.fmm_workers} workers, FMM order 20 inner / 40 FP64 "
                                   f"residuals)" if hybrid
                                   else ("the configurations below %d nodes only, all in the fused "
-                                        "direct engine" % args.fmm_min_nodes if engine_only
+                                        "direct engine" % min_nodes if engine_only
                                         else "every configuration in the fused direct engine")),
                    "configs": len(cfgs), "total_nodes": int(N.sum()),
                    "parallelism": "single GPU"},
@@ -539,8 +616,11 @@ def bench_batch(args):
         "setup_s": t_setup, "autotune": {"persist_blocks": pblk, "far_want": fwant},
         "gmres_iterations_mean": float(its.mean()), "gmres_iterations_max": int(its.max()),
         "refine_steps_max": int(ref.max()), "residual_max": resid,
-        "matvec_interactions_per_s_fp32": pairs32 / (ms32 * 1e-3) if ms32 > 0 else None,
-        "matvec_interactions_per_s_fp64": pairs64 / (ms64 * 1e-3) if ms64 > 0 else None,
+        "matvec_interactions_per_s_fp32": (pairs32 / (ms32 * 1e-3) if ms32 > 0 and pairs32 > 0
+                                           else None),
+        "leaf_pass_interactions_per_s_fp32": pairsl32 / (msl32 * 1e-3) if msl32 > 0 else None,
+        "matvec_interactions_per_s_fp64": (pairs64 / (ms64 * 1e-3) if ms64 > 0 and pairs64 > 0
+                                           else None),
         "fp64_one_at_a_time": {"sample": len(sample), "of": len(cfgs),
                                "solves_per_s": len(cfgs) / t_one,
                                "latency_ms_p50": float(np.percentile(service, 50)) * 1e3,
@@ -548,24 +628,7 @@ def bench_batch(args):
                                "all_configs_one_after_another_ms": t_one * 1e3},
         "errors_vs_fp64_path": dict(err, configs=len(ref_idx), reference="FP64 solve to 1e-12"),
         "errors_vs_oracle": errors_vs_oracle_c2(yq, tol),
-        "roofline": {"bound": "alu", "kernel": "bsym32_kernel" if sym else "bfar32_kernel",
-                     "achieved": achieved / 1e12,
-                     "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32,
-                     "traffic": (bc["hbm_bytes_per_pair"] * pairs32 / max(n32, 1)
-                                 if "hbm_bytes_per_pair" in bc else None),
-                     "flops_per_pair": F32_ALG,
-                     "counter_flops_per_pair": bc.get("valu_flops_per_pair"),
-                     "counter_frac": (bc["valu_flops_per_pair"] * pairs32 / (ms32 * 1e-3) / PEAK_FP32
-                                      if "valu_flops_per_pair" in bc and ms32 > 0 else None),
-                     "pairs_per_launch": pairs32 / max(n32, 1), "avg_launch_ms": avg32,
-                     "launches": n32,
-                     "fp64_kernel": {"kernel": "bfar64_kernel", "launches": n64,
-                                     "avg_launch_ms": ms64 / max(n64, 1),
-                                     "achieved": F64_ALG * pairs64 / (ms64 * 1e-3) / 1e12
-                                     if ms64 > 0 else None,
-                                     "peak": PEAK_FP64 / 1e12,
-                                     "frac": F64_ALG * pairs64 / (ms64 * 1e-3) / PEAK_FP64
-                                     if ms64 > 0 else None}},
+        "roofline": roof,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_batch(cfgs, mv)
@@ -603,7 +666,7 @@ def bench_serve(args):
     prm = yq.default_params(panels_per_particle=32, qbx_order=10, tol=1e-8, precision=yq.YQ_MIXED,
                             restart=60, maxiter=300, far_mode=yq.YQ_FAR_AUTO)
     srv = yq.Server(prm, node_capacity=2_000_000, max_slots=48, mem_budget_bytes=150e9)
-    thr = args.fmm_min_nodes
+    thr = args.fmm_min_nodes if args.fmm_min_nodes is not None else SINGLE_FMM_NODES
     srv.set_fmm(thr, workers=args.fmm_workers)
     # warm-up requests of both lanes (code paths, allocations)
     small = min(range(len(parts)), key=lambda k: parts[k].n)

@@ -415,19 +415,25 @@ int yq_batch_autotune(yq_batch* batch, int32_t* persist_blocks, int32_t* far_wan
 /* enable != 0: replay the captured iteration graph (default); 0: launch eagerly. */
 int yq_batch_use_graphs(yq_batch* batch, int32_t enable);
 
-/* Timers of the fused engine's far-field launches (the FP32 kernel of the inner
- * iterations and the FP64 kernel of the refinement residuals).  enable != 0:
- * every launch is bracketed by hipEvents on the batch's stream (the captured
- * iteration is then replayed as three graphs, with the events recorded between
- * the launch of the far-field kernel's graph and its neighbours) and the launches
- * count the source-target pairs they evaluate (masked configurations excluded).
- * yq_batch_profile_read synchronises and returns, for YQ_MIXED (FP32 kernel) or
- * YQ_FP64, the number of timed launches, their summed duration (ms) and the
- * summed pairs; reset != 0 clears them.  Configurations of the FMM lane are not
- * counted.  Both synchronous. */
+/* Timers of the fused engine's far-field launches: the direct members' fused
+ * far field (the FP32 kernel of the inner iterations, the FP64 kernel of the
+ * refinement residuals) and the FMM forest's leaf pass (direct interactions of
+ * neighbouring leaves and the local expansions; inner order in FP32 pairs,
+ * residual order in FP64).  enable != 0: every such launch (the leaf pass: its
+ * launches of one operator application together) is bracketed by hipEvents on
+ * the batch's stream (the captured iteration is then replayed as one graph per
+ * part, with the events recorded between their launches) and the launches count
+ * the source-target pairs they evaluate (masked configurations excluded; the leaf
+ * pass counts the pairs of every leaf with the leaves of its direct-interaction
+ * list).  yq_batch_profile_read (direct far field) and yq_batch_profile_read_leaf
+ * (leaf pass) synchronise and return, for YQ_MIXED or YQ_FP64, the number of
+ * timed launches, their summed duration (ms) and the summed pairs; reset != 0
+ * clears them.  Configurations of the FMM lane are not counted.  All synchronous. */
 int yq_batch_profile_enable(yq_batch* batch, int32_t enable);
 int yq_batch_profile_read(yq_batch* batch, int32_t precision, int64_t* launches,
                           double* total_ms, double* pairs, int32_t reset);
+int yq_batch_profile_read_leaf(yq_batch* batch, int32_t precision, int64_t* launches,
+                               double* total_ms, double* pairs, int32_t reset);
 
 /* ---- Serving -----------------------------------------------------------------------------
  * A continuous-batching solve server on one GPU.  Requests (one particle

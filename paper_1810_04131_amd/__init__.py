@@ -386,12 +386,15 @@ class Batch:
         """Timers of the fused far-field launches (see yq_batch_profile_enable)."""
         self._check(self.lib.yq_batch_profile_enable(self.h, int(bool(enable))))
 
-    def profile_read(self, precision=YQ_MIXED, reset=True):
-        """(launches, total ms, source-target pairs) of the timed far-field launches."""
+    def profile_read(self, precision=YQ_MIXED, reset=True, kernel="direct"):
+        """(launches, total ms, source-target pairs) of the timed far-field launches:
+        kernel "direct" (the direct members' fused far field) or "leaf" (the FMM
+        forest's leaf pass)."""
+        fn = {"direct": self.lib.yq_batch_profile_read,
+              "leaf": self.lib.yq_batch_profile_read_leaf}[kernel]
         n, ms, pairs = ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
-        self._check(self.lib.yq_batch_profile_read(self.h, int(precision), ctypes.byref(n),
-                                                   ctypes.byref(ms), ctypes.byref(pairs),
-                                                   int(bool(reset))))
+        self._check(fn(self.h, int(precision), ctypes.byref(n), ctypes.byref(ms),
+                       ctypes.byref(pairs), int(bool(reset))))
         return int(n.value), float(ms.value), float(pairs.value)
 
     def segment(self, v, c):

@@ -10,6 +10,13 @@ namespace yq {
 
 constexpr int SC = 1024;   // nodes per chunk of the symmetric FP32 far field (bsym32)
 
+// matvec parts: the FMM members' expansions (and the FP32 source records), the
+// forest's leaf pass, the direct members' fused far field, the finish; the timers
+// bracket the two middle ones
+constexpr int NPART = 4;
+constexpr int PART_LEAF = 1, PART_DIRECT = 2;
+constexpr int PK_DIRECT = 0, PK_LEAF = 1;
+
 // What the fused kernels need of one configuration (device copy, one per config).
 struct ConfDev {
   const double* x;
@@ -86,13 +93,16 @@ struct Engine {
   // leaf pairs and M2L) and the FP64 residual operator (the members' order-40 FMMs)
   FmmForest forest_in, forest_hi;
   hipGraphExec_t graph_exec[2] = {nullptr, nullptr};   // FP64, mixed iteration
-  hipGraphExec_t graph_part[6] = {};                    // the same in three parts (timers on)
-  // timers of the fused far-field launches: events around every launch and the
-  // number of source-target pairs the launches evaluated, per precision
+  hipGraphExec_t graph_part[2 * NPART] = {};            // the same in parts (timers on)
+  // timers: events around every launch of the direct members' fused far field (kind
+  // PK_DIRECT) and of the forest's leaf pass (PK_LEAF), and the number of
+  // source-target pairs the launches evaluated, per precision and kind
   bool prof_on = false;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev[2];
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev[2][2];
   std::vector<hipEvent_t> ev_pool;
-  DevBuf<unsigned long long> prof_pairs;
+  DevBuf<unsigned long long> prof_pairs;   // [precision * 2 + kind]
+  unsigned long long* prof_counter(int prec, int kind) const;
+  void prof_record(int prec, int kind, hipEvent_t a, hipEvent_t b);
 
   ~Engine();
   void init(const yq_params& p);
@@ -105,7 +115,7 @@ struct Engine {
   void drop_graphs();
   hipEvent_t prof_event();
   void set_profiling(bool on);
-  void read_profile(int prec, int64_t& launches, double& ms, double& pairs, bool reset);
+  void read_profile(int prec, int kind, int64_t& launches, double& ms, double& pairs, bool reset);
   void dots(const int* mask, const double* x, const double* y);
   void axpby(const int* mask, double a, const double* x, double b, const double* y, double* out);
   void iteration(int prec);

@@ -737,11 +737,12 @@ static inline unsigned nb256(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 Engine::~Engine() {
   drop_graphs();
-  for (auto& v : prof_ev)
-    for (auto& e : v) {
-      (void)hipEventDestroy(e.first);
-      (void)hipEventDestroy(e.second);
-    }
+  for (auto& pv : prof_ev)
+    for (auto& v : pv)
+      for (auto& e : v) {
+        (void)hipEventDestroy(e.first);
+        (void)hipEventDestroy(e.second);
+      }
   for (auto e : ev_pool) (void)hipEventDestroy(e);
   if (own_stream && stream) (void)hipStreamDestroy(stream);
 }
@@ -922,21 +923,32 @@ int Engine::grid_blocks(int n) const {
   return std::max(1, std::min(n, want));
 }
 
-// The three parts of out = A sigma (precision prec) for configurations in mask,
-// input column from V/col: 0 packs the FP32 source records (mixed only) and runs
-// the FMM members' forest, 1 the fused far-field kernel of the direct members, 2
-// the chunk sums (or the forest's far field) and near correction.
+unsigned long long* Engine::prof_counter(int prec, int kind) const {
+  return prof_on ? prof_pairs.p + 2 * (prec == YQ_MIXED ? 1 : 0) + kind : nullptr;
+}
+
+void Engine::prof_record(int prec, int kind, hipEvent_t a, hipEvent_t b) {
+  prof_ev[prec == YQ_MIXED ? 1 : 0][kind].push_back({a, b});
+}
+
+// The parts of out = A sigma (precision prec) for configurations in mask, input
+// column from V/col: 0 packs the FP32 source records (mixed only) and computes the
+// FMM members' expansions (inner operator, or the FP64 residual operator), 1 their
+// leaf pass, 2 the fused far-field kernel of the direct members, 3 the chunk sums
+// (or the forest's far field) and near correction.
 void Engine::matvec_part(int part, int prec, const int* mask, const double* Vin, const int* col,
                          double* out) {
-  unsigned long long* pc = prof_on ? prof_pairs.p + (prec == YQ_MIXED ? 1 : 0) : nullptr;
+  const FmmForest& fo = prec == YQ_MIXED ? forest_in : forest_hi;
   if (part == 0) {
     if (prec == YQ_MIXED && nitems > 0)
       bpack32_kernel<<<nb256(T), 256, 0, stream>>>(conf.p, node_conf.p, T, mask, Vin, col,
                                                    sym32 ? 1 : 0);
-    // the FMM members' far field (inner operator, or the FP64 residual operator)
-    (prec == YQ_MIXED ? forest_in : forest_hi).apply(mask, Vin, col, T, stream);
-  } else if (part == 1) {
+    fo.expansions(mask, Vin, col, T, stream);
+  } else if (part == PART_LEAF) {
+    fo.leaves(mask, stream, prof_counter(prec, PK_LEAF));
+  } else if (part == PART_DIRECT) {
     if (nitems == 0) return;
+    unsigned long long* pc = prof_counter(prec, PK_DIRECT);
     if (prec == YQ_MIXED && sym32)
       bsym32_kernel<<<grid_blocks(nsitems), BB, 0, stream>>>(conf.p, sitems.p, nsitems, mask, pc);
     else if (prec == YQ_MIXED)
@@ -951,18 +963,20 @@ void Engine::matvec_part(int part, int prec, const int* mask, const double* Vin,
   YQ_HIP(hipGetLastError());
 }
 
-// out = A sigma; with the timers on, the far-field launch is bracketed by events.
+// out = A sigma; with the timers on, the leaf pass and the direct far-field launch
+// are bracketed by events.
 void Engine::matvec(int prec, const int* mask, const double* Vin, const int* col, double* out) {
-  matvec_part(0, prec, mask, Vin, col, out);
-  hipEvent_t a = prof_on ? prof_event() : nullptr;
-  if (a) YQ_HIP(hipEventRecord(a, stream));
-  matvec_part(1, prec, mask, Vin, col, out);
-  if (a) {
-    hipEvent_t b = prof_event();
-    YQ_HIP(hipEventRecord(b, stream));
-    prof_ev[prec == YQ_MIXED ? 1 : 0].push_back({a, b});
+  for (int part = 0; part < NPART; ++part) {
+    const int kind = part == PART_LEAF ? PK_LEAF : part == PART_DIRECT ? PK_DIRECT : -1;
+    hipEvent_t a = prof_on && kind >= 0 ? prof_event() : nullptr;
+    if (a) YQ_HIP(hipEventRecord(a, stream));
+    matvec_part(part, prec, mask, Vin, col, out);
+    if (a) {
+      hipEvent_t b = prof_event();
+      YQ_HIP(hipEventRecord(b, stream));
+      prof_record(prec, kind, a, b);
+    }
   }
-  matvec_part(2, prec, mask, Vin, col, out);
 }
 
 // nrm[c] = x_c . y_c for masked configurations (device)
@@ -983,19 +997,19 @@ void Engine::axpby(const int* mask, double a, const double* x, double b, const d
 
 // One Arnoldi step for every active configuration (the captured sequence).
 void Engine::iteration(int prec) {
-  for (int part = 0; part < 3; ++part) iteration_part(prec, part);
+  for (int part = 0; part < NPART; ++part) iteration_part(prec, part);
 }
 
-// Parts 0 and 1 of an Arnoldi step are those of its matvec; part 2 is the rest
-// of the matvec and the orthogonalisation, Givens step and normalisation.
+// The parts of an Arnoldi step are those of its matvec; the last one also holds the
+// orthogonalisation, Givens step and normalisation.
 void Engine::iteration_part(int prec, int part) {
-  if (part < 2) {
+  if (part < NPART - 1) {
     matvec_part(part, prec, active.p, V.p, jc.p, w.p);
     return;
   }
   const int nc = (int)members.size();
   const int hs = 2 * (m + 1) + 2;
-  matvec_part(2, prec, active.p, V.p, jc.p, w.p);
+  matvec_part(NPART - 1, prec, active.p, V.p, jc.p, w.p);
   for (int pass = 0; pass < 2; ++pass) {
     bmultidot_kernel<<<nkblk, KB2, 0, stream>>>(conf.p, kblk.p, V.p, T, jc.p, w.p, active.p,
                                                 kpart.p);
@@ -1050,42 +1064,39 @@ void Engine::ensure_graphs() {
     if (!prof_on) {
       if (!graph_exec[gi]) capture_iteration(*this, prec, -1, graph_exec[gi]);
     } else {
-      for (int part = 0; part < 3; ++part)
-        if (!graph_part[3 * gi + part]) capture_iteration(*this, prec, part, graph_part[3 * gi + part]);
+      for (int part = 0; part < NPART; ++part)
+        if (!graph_part[NPART * gi + part])
+          capture_iteration(*this, prec, part, graph_part[NPART * gi + part]);
     }
   }
 }
 
 // One iteration: a replay of the captured graph.  With the timers on, the
-// iteration is captured as three graphs (before, the far-field kernel, after)
-// and events recorded between their launches bracket the far-field kernel.
+// iteration is captured as one graph per part, and events recorded between their
+// launches bracket the leaf pass and the direct far-field kernel.
 void Engine::run_iteration(int prec) {
   const int gi = prec == YQ_MIXED ? 1 : 0;
-  if (!use_graphs) {
-    iteration_part(prec, 0);
-    hipEvent_t a = prof_on ? prof_event() : nullptr;
+  if (use_graphs) {
+    ensure_graphs();
+    if (!prof_on) {
+      YQ_HIP(hipGraphLaunch(graph_exec[gi], stream));
+      return;
+    }
+  }
+  for (int part = 0; part < NPART; ++part) {
+    const int kind = part == PART_LEAF ? PK_LEAF : part == PART_DIRECT ? PK_DIRECT : -1;
+    hipEvent_t a = prof_on && kind >= 0 ? prof_event() : nullptr;
     if (a) YQ_HIP(hipEventRecord(a, stream));
-    iteration_part(prec, 1);
+    if (use_graphs)
+      YQ_HIP(hipGraphLaunch(graph_part[NPART * gi + part], stream));
+    else
+      iteration_part(prec, part);
     if (a) {
       hipEvent_t b = prof_event();
       YQ_HIP(hipEventRecord(b, stream));
-      prof_ev[gi].push_back({a, b});
+      prof_record(prec, kind, a, b);
     }
-    iteration_part(prec, 2);
-    return;
   }
-  ensure_graphs();
-  if (!prof_on) {
-    YQ_HIP(hipGraphLaunch(graph_exec[gi], stream));
-    return;
-  }
-  YQ_HIP(hipGraphLaunch(graph_part[3 * gi], stream));
-  hipEvent_t a = prof_event(), b = prof_event();
-  YQ_HIP(hipEventRecord(a, stream));
-  YQ_HIP(hipGraphLaunch(graph_part[3 * gi + 1], stream));
-  YQ_HIP(hipEventRecord(b, stream));
-  prof_ev[gi].push_back({a, b});
-  YQ_HIP(hipGraphLaunch(graph_part[3 * gi + 2], stream));
 }
 
 hipEvent_t Engine::prof_event() {
@@ -1105,34 +1116,36 @@ void Engine::set_profiling(bool on) {
   drop_graphs();   // the captured sequence changes with the timers
   prof_on = on;
   if (on && !prof_pairs.p) {
-    prof_pairs.alloc(2);
-    YQ_HIP(hipMemsetAsync(prof_pairs.p, 0, 2 * sizeof(unsigned long long), stream));
+    prof_pairs.alloc(4);
+    YQ_HIP(hipMemsetAsync(prof_pairs.p, 0, 4 * sizeof(unsigned long long), stream));
     YQ_HIP(hipStreamSynchronize(stream));
   }
 }
 
-void Engine::read_profile(int prec, int64_t& launches, double& ms, double& pairs, bool reset) {
+void Engine::read_profile(int prec, int kind, int64_t& launches, double& ms, double& pairs,
+                          bool reset) {
   const int gi = prec == YQ_MIXED ? 1 : 0;
+  auto& ev = prof_ev[gi][kind];
   YQ_HIP(hipStreamSynchronize(stream));
-  launches = (int64_t)prof_ev[gi].size();
+  launches = (int64_t)ev.size();
   ms = 0.0;
-  for (auto& e : prof_ev[gi]) {
+  for (auto& e : ev) {
     float t = 0.0f;
     YQ_HIP(hipEventElapsedTime(&t, e.first, e.second));
     ms += t;
   }
-  unsigned long long pc[2] = {0, 0};
+  unsigned long long pc[4] = {0, 0, 0, 0};
   if (prof_pairs.p)
-    YQ_HIP(hipMemcpy(pc, prof_pairs.p, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost));
-  pairs = (double)pc[gi];
+    YQ_HIP(hipMemcpy(pc, prof_pairs.p, 4 * sizeof(unsigned long long), hipMemcpyDeviceToHost));
+  pairs = (double)pc[2 * gi + kind];
   if (reset) {
-    for (auto& e : prof_ev[gi]) {
+    for (auto& e : ev) {
       ev_pool.push_back(e.first);
       ev_pool.push_back(e.second);
     }
-    prof_ev[gi].clear();
+    ev.clear();
     if (prof_pairs.p) {
-      YQ_HIP(hipMemsetAsync(prof_pairs.p + gi, 0, sizeof(unsigned long long), stream));
+      YQ_HIP(hipMemsetAsync(prof_pairs.p + 2 * gi + kind, 0, sizeof(unsigned long long), stream));
       YQ_HIP(hipStreamSynchronize(stream));
     }
   }
@@ -1340,10 +1353,19 @@ void Engine::resid(const std::vector<int>& plain, const std::vector<int>& fused,
   upload_mask(pmask, plain);
   upload_mask(fmask, fused);
   forest_hi.expansions(inc.p, x, nullptr, T, stream);
-  forest_hi.leaves(inc.p, stream);
+  {
+    hipEvent_t a = prof_on ? prof_event() : nullptr;
+    if (a) YQ_HIP(hipEventRecord(a, stream));
+    forest_hi.leaves(inc.p, stream, prof_counter(YQ_FP64, PK_LEAF));
+    if (a) {
+      hipEvent_t b = prof_event();
+      YQ_HIP(hipEventRecord(b, stream));
+      prof_record(YQ_FP64, PK_LEAF, a, b);
+    }
+  }
   forest_hi.leaves_grad(fmask.p, stream);
   if (nitems) {
-    unsigned long long* pc = prof_on ? prof_pairs.p : nullptr;
+    unsigned long long* pc = prof_counter(YQ_FP64, PK_DIRECT);
     hipEvent_t a = prof_on ? prof_event() : nullptr;
     if (a) YQ_HIP(hipEventRecord(a, stream));
     bfar64_kernel<<<grid_blocks(nitems), BB, 0, stream>>>(conf.p, items.p, nitems, pmask.p, x, nullptr, T,
@@ -1351,7 +1373,7 @@ void Engine::resid(const std::vector<int>& plain, const std::vector<int>& fused,
     if (a) {
       hipEvent_t b = prof_event();
       YQ_HIP(hipEventRecord(b, stream));
-      prof_ev[0].push_back({a, b});
+      prof_record(YQ_FP64, PK_DIRECT, a, b);
     }
     bfused64_kernel<<<grid_blocks(nitems), BB, 0, stream>>>(conf.p, items.p, nitems, fmask.p, x, nullptr,
                                                       T, tab64.p);

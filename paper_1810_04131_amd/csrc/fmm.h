@@ -175,7 +175,8 @@ struct FmmForest {
   // passes after them: far field (leaves) or its gradient (leaves_grad, FP64 forests)
   void expansions(const int* mask, const double* V, const int* col, int64_t T,
                   hipStream_t s) const;
-  void leaves(const int* mask, hipStream_t s) const;
+  // pairs (may be null): adds the source-target pairs the leaf pass evaluates
+  void leaves(const int* mask, hipStream_t s, unsigned long long* pairs = nullptr) const;
   void leaves_grad(const int* mask, hipStream_t s) const;
 };
 

@@ -1548,11 +1548,17 @@ template <bool F32, int NW>
 __global__ __launch_bounds__(FB * NW) void forest_leaf_kernel(const FmmDev* __restrict__ fd,
                                                               const int2* __restrict__ items,
                                                               const int* __restrict__ mask, int p,
-                                                              int use_col) {
+                                                              int use_col,
+                                                              unsigned long long* __restrict__ pairs) {
   extern __shared__ double sh[];
   const int2 it = items[blockIdx.x];
   const FmmDev& d = fd[it.x];
   if (!mask[d.cfg]) return;
+  if (pairs && threadIdx.x == 0) {   // profiling: targets x the sources of the leaf's P2P list
+    unsigned long long ns = 0;
+    for (int e = d.nbp[it.y]; e < d.nbp[it.y + 1]; ++e) ns += (unsigned long long)d.leaf_cnt[d.nbi[e]];
+    atomicAdd(pairs, ns * (unsigned long long)d.leaf_cnt[it.y]);
+  }
   leaf_pass<F32, NW>(it.y, p, d.kappa, 1, use_col, d.leaf_start, d.leaf_cnt, d.leaf_gid, d.nbp,
                      d.nbi, d.leaf_cx, d.leaf_cy, d.Lall, d.xs, d.ys, d.qx, d.qy, d.perm, d.tab,
                      d.out, sh);
@@ -1698,17 +1704,18 @@ void FmmForest::apply(const int* mask, const double* V, const int* col, int64_t 
   leaves(mask, s);
 }
 
-void FmmForest::leaves(const int* mask, hipStream_t s) const {
+void FmmForest::leaves(const int* mask, hipStream_t s, unsigned long long* pairs) const {
   if (nmem == 0) return;
   const int use_col = p <= kColMaxOrder;
   if (n_leaf2) {
     auto k = f32 ? forest_leaf_kernel<true, 2> : forest_leaf_kernel<false, 2>;
-    k<<<n_leaf2, FB * 2, leaf_lds_bytes(2, p, use_col), s>>>(dev.p, it_leaf2.p, mask, p, use_col);
+    k<<<n_leaf2, FB * 2, leaf_lds_bytes(2, p, use_col), s>>>(dev.p, it_leaf2.p, mask, p, use_col,
+                                                             pairs);
   }
   if (n_leaf4) {
     auto k = f32 ? forest_leaf_kernel<true, PW> : forest_leaf_kernel<false, PW>;
     k<<<n_leaf4, FB * PW, leaf_lds_bytes(PW, p, use_col), s>>>(dev.p, it_leaf4.p, mask, p,
-                                                               use_col);
+                                                               use_col, pairs);
   }
   YQ_HIP(hipGetLastError());
 }

@@ -469,3 +469,36 @@ def test_batch_symmetric_far_field_matches_directed_and_oracle(panels):
     assert all(i["residual"] <= 1e-10 for i in infos)
     assert _rel(_np(ss), _np(sf)) < 1e-8
     torch.cuda.synchronize()
+
+
+def test_batch_leaf_pass_timers_count_pairs_and_leave_results_unchanged():
+    """The forest's leaf-pass timers: one timed launch per operator application, the
+    same pair count at both orders (one tree), bounded by the members' N^2, and a
+    profiled solve (iteration graph split into parts) equal to the plain one."""
+    _torch()
+    cfgs = _forest_configs()
+    prm = dict(panels_per_particle=P, qbx_order=ORDER, tol=1e-10, precision=1)
+    ref = _lane_batch(cfgs, True, **prm)
+    ref.set_boundary_data(ref.boundary_label())
+    s_ref, i_ref = ref.solve()
+    b = _lane_batch(cfgs, True, **prm)
+    b.profile(True)
+    N = np.diff(b.offsets)
+    tree = N >= 5 * P * 16
+    assert tree.sum() == 2
+    x = np.random.default_rng(5).standard_normal(b.total)
+    b.apply_operator(x, yq.YQ_MIXED)
+    n1, ms1, p1 = b.profile_read(yq.YQ_MIXED, reset=False, kernel="leaf")
+    b.apply_operator(x, yq.YQ_MIXED)
+    n2, ms2, p2 = b.profile_read(yq.YQ_MIXED, kernel="leaf")
+    assert n1 == 1 and n2 == 2 and 0.0 < ms1 < ms2 and p2 == 2 * p1
+    assert float(N[tree].sum()) < p1 <= float((N[tree] ** 2).sum())
+    b.apply_operator(x, yq.YQ_FP64)
+    n64, ms64, p64 = b.profile_read(yq.YQ_FP64, kernel="leaf")
+    assert n64 == 1 and ms64 > 0.0 and p64 == p1
+    b.set_boundary_data(b.boundary_label())
+    s, infos = b.solve()
+    assert np.array_equal(_np(s), _np(s_ref))
+    assert [i["iterations"] for i in infos] == [i["iterations"] for i in i_ref]
+    n, ms, pairs = b.profile_read(yq.YQ_MIXED, kernel="leaf")
+    assert n >= max(i["matvecs_fp32"] for i in infos) and 0 < pairs <= n * p1
