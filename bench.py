@@ -151,6 +151,9 @@ def parse():
                     help="batch: inner far field of the direct members with one kernel "
                          "evaluation per unordered pair (bsym32_kernel) or per directed pair "
                          "(bfar32_kernel)")
+    ap.add_argument("--near-cache-gb", type=float, default=None,
+                    help="batch: device memory for the FMM trees' near-field caches (GB; 0 "
+                         "none; default: the library's, half of the free memory)")
     ap.add_argument("--fmm-min-nodes", type=int, default=None,
                     help="batch: configurations of at least this many nodes take the FMM "
                          "(default 0 for hybrid: every configuration is a tree of the forest, "
@@ -437,6 +440,8 @@ def bench_batch(args):
                             precision=yq.YQ_MIXED, restart=60, maxiter=300)
     b = yq.Batch(prm)
     b.set_symmetric_far(args.far32 == "symmetric")
+    if args.near_cache_gb is not None:
+        b.set_near_cache(int(args.near_cache_gb * 1e9))
     if hybrid:
         b.set_fmm(thr, workers=args.fmm_workers, in_engine=forest)
     t0 = time.perf_counter()
@@ -445,6 +450,8 @@ def bench_batch(args):
     N = np.diff(b.offsets).astype(float)
     lane = N >= thr if hybrid else np.zeros(len(cfgs), dtype=bool)
     log(f"set-up {t_setup:.1f} s, {b.total} nodes, {int(lane.sum())} configurations take the FMM")
+    near = b.near_cache_info()
+    log(f"near-field caches: {near[0] / 1e9:.1f} GB, {near[1]} FP32 / {near[2]} FP64 trees")
     pblk, fwant = b.autotune()
     log(f"autotuned: persistent blocks {pblk}, far_want {fwant}")
     b.set_boundary_data(b.boundary_label())
@@ -614,6 +621,7 @@ def bench_batch(args):
         "solves_per_s": len(cfgs) / t_step,
         "latency_ms_p50": percentile(lat, 0.5) * 1e3, "latency_ms_p99": percentile(lat, 0.99) * 1e3,
         "setup_s": t_setup, "autotune": {"persist_blocks": pblk, "far_want": fwant},
+        "near_cache": {"bytes": near[0], "trees_fp32": near[1], "trees_fp64": near[2]},
         "gmres_iterations_mean": float(its.mean()), "gmres_iterations_max": int(its.max()),
         "refine_steps_max": int(ref.max()), "residual_max": resid,
         "matvec_interactions_per_s_fp32": (pairs32 / (ms32 * 1e-3) if ms32 > 0 and pairs32 > 0

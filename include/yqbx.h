@@ -361,6 +361,21 @@ int yq_batch_set_fmm(yq_batch* batch, int64_t min_nodes, int32_t workers);
  * yq_batch_set_configs (YQ_ESTATE after). */
 int yq_batch_set_fmm_engine(yq_batch* batch, int32_t enable);
 
+/* Near-field cache of the FMM forest's trees: the leaf passes' pair coefficients
+ * K1(z)/z ((x - y) . w nu) of every pair of neighbouring leaves (section 5's
+ * direct interactions of the FMM) are computed once per geometry, in FP32 for the
+ * inner operator and in FP64 for the residual operator, and the passes then read
+ * them instead of evaluating K1 (a block-sparse matrix-vector product).
+ * max_bytes: the most device memory the caches may hold (FP32 caches of every tree
+ * first, then FP64 ones, in configuration order, while they fit); 0 disables; -1
+ * (default): half of the device memory free when the configurations are set.
+ * Results agree with the uncached passes to rounding.  Before yq_batch_set_configs
+ * (YQ_ESTATE after).  yq_batch_near_cache_info: bytes held and the number of
+ * trees with an FP32 / FP64 cache (outputs may be NULL). */
+int yq_batch_set_near_cache(yq_batch* batch, int64_t max_bytes);
+int yq_batch_near_cache_info(const yq_batch* batch, int64_t* bytes, int32_t* trees32,
+                             int32_t* trees64);
+
 /* Inner (FP32) far field of the direct members.  enable != 0 (default): one
  * evaluation of K1(z)/z per unordered node pair serves both directions of the
  * double-layer sum (section 4, eq. double-layer-def: K1(z)/z depends on the

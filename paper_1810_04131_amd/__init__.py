@@ -283,6 +283,19 @@ class Batch:
         self._check(self.lib.yq_batch_set_fmm_engine(self.h, int(bool(in_engine))))
         return self
 
+    def set_near_cache(self, max_bytes=-1):
+        """Device memory for the FMM trees' near-field caches (before set_configs):
+        -1 half of the free memory (default), 0 none."""
+        self._check(self.lib.yq_batch_set_near_cache(self.h, int(max_bytes)))
+        return self
+
+    def near_cache_info(self):
+        """(bytes held, trees with an FP32 cache, trees with an FP64 cache)."""
+        b, t32, t64 = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32()
+        self._check(self.lib.yq_batch_near_cache_info(self.h, ctypes.byref(b), ctypes.byref(t32),
+                                                      ctypes.byref(t64)))
+        return int(b.value), int(t32.value), int(t64.value)
+
     def set_symmetric_far(self, enable=True):
         """Inner far field: one evaluation per unordered pair (default) or per directed
         pair (before set_configs)."""

@@ -126,6 +126,9 @@ SIGNATURES = {
     "yq_batch_set_fmm": (c_int32, [P, c_int64, c_int32]),
     "yq_batch_set_fmm_engine": (c_int32, [P, c_int32]),
     "yq_batch_set_symmetric_far": (c_int32, [P, c_int32]),
+    "yq_batch_set_near_cache": (c_int32, [P, c_int64]),
+    "yq_batch_near_cache_info": (c_int32, [P, ctypes.POINTER(c_int64), ctypes.POINTER(c_int32),
+                                           ctypes.POINTER(c_int32)]),
     "yq_batch_set_configs": (c_int32, [P, c_int32, P, P, P, P, P]),
     "yq_batch_num_nodes": (c_int32, [P, ctypes.POINTER(c_int64), P]),
     "yq_batch_boundary_label": (c_int32, [P, c_int32, c_double, c_double, P]),

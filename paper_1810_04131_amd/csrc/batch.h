@@ -92,6 +92,12 @@ struct Engine {
   // members with an FMM far field, as one forest per operator: the inner (FP32
   // leaf pairs and M2L) and the FP64 residual operator (the members' order-40 FMMs)
   FmmForest forest_in, forest_hi;
+  // near-field caches of the forest trees (FP32 coefficients for the inner operator
+  // first, then FP64 for the residual operator): at most this many bytes; -1: half of
+  // the device memory free at the rebuild (with the caches already held)
+  int64_t near_budget = -1;
+  int64_t near_bytes = 0;      // bytes the caches hold
+  int near_trees32 = 0, near_trees64 = 0;
   hipGraphExec_t graph_exec[2] = {nullptr, nullptr};   // FP64, mixed iteration
   hipGraphExec_t graph_part[2 * NPART] = {};            // the same in parts (timers on)
   // timers: events around every launch of the direct members' fused far field (kind

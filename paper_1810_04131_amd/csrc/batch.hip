@@ -860,6 +860,38 @@ void Engine::rebuild() {
   if (nfitems)
     YQ_HIP(hipMemcpyAsync(fitems.p, fi.data(), nfitems * sizeof(int2), hipMemcpyHostToDevice, stream));
   pen.alloc(std::max<int64_t>(npart, 1));
+  // near-field caches within the budget, FP32 (inner operator, every iteration)
+  // first; a tree keeps its cache until its geometry changes
+  {
+    int64_t held = 0;
+    for (auto* tv : {&tin, &thi})
+      for (auto& t : *tv)
+        if (t.fmm->nc_kind)
+          held += t.fmm->p2p_pairs * (t.fmm->nc_kind == 2 ? 8 : 4) + t.fmm->N * 8;
+    int64_t budget = near_budget;
+    if (budget < 0) {
+      size_t fr = 0, tot = 0;
+      YQ_HIP(hipMemGetInfo(&fr, &tot));
+      budget = ((int64_t)fr + held) / 2;
+    }
+    int64_t used = 0;
+    near_trees32 = near_trees64 = 0;
+    for (int pass = 0; pass < 2; ++pass) {
+      const bool f64 = pass == 1;
+      for (auto& t : f64 ? thi : tin) {
+        const int want = f64 ? 2 : 1;
+        const int64_t need = t.fmm->p2p_pairs * (f64 ? 8 : 4) + t.fmm->N * 8;
+        if (used + need <= budget) {
+          if (t.fmm->nc_kind != want) t.fmm->build_near_cache(f64, t.tab, stream);
+          used += need;
+          (f64 ? near_trees64 : near_trees32) += 1;
+        } else if (t.fmm->nc_kind) {
+          t.fmm->drop_near_cache();
+        }
+      }
+    }
+    near_bytes = used;
+  }
   forest_in.build(tin, true, stream);
   forest_hi.build(thi, false, stream);
   conf.alloc(std::max(nc, 1));

@@ -404,6 +404,25 @@ int yq_batch_set_fmm_engine(yq_batch* b, int32_t enable) {
   });
 }
 
+int yq_batch_set_near_cache(yq_batch* b, int64_t max_bytes) {
+  return bguard(b, [&] {
+    YQ_REQUIRE(b, YQ_EINVAL, "null batch");
+    YQ_REQUIRE(max_bytes >= -1, YQ_EINVAL, "max_bytes must be >= -1");
+    YQ_REQUIRE(!b->ready, YQ_ESTATE, "the near-field cache budget is set before yq_batch_set_configs");
+    b->eng.near_budget = max_bytes;
+  });
+}
+
+int yq_batch_near_cache_info(const yq_batch* b, int64_t* bytes, int32_t* trees32,
+                             int32_t* trees64) {
+  return bguard(const_cast<yq_batch*>(b), [&] {
+    YQ_REQUIRE(b, YQ_EINVAL, "null batch");
+    if (bytes) *bytes = b->eng.near_bytes;
+    if (trees32) *trees32 = b->eng.near_trees32;
+    if (trees64) *trees64 = b->eng.near_trees64;
+  });
+}
+
 int yq_batch_set_symmetric_far(yq_batch* b, int32_t enable) {
   return bguard(b, [&] {
     YQ_REQUIRE(b, YQ_EINVAL, "null batch");

@@ -105,13 +105,16 @@ __device__ __forceinline__ double expm64(double z, const double* __restrict__ T)
   return ldexp(hornerT<12>(T + T_EX, r), -(int)k);
 }
 
+// K1(z)/z for z^2 = z2 < 4 (the ascending series).
+__device__ __forceinline__ double k1z_64_small(double z2, const double* __restrict__ T) {
+  double t = 0.25 * z2;
+  double lt = log(t);
+  return 0.25 * rcp64(t) + 0.25 * (lt * hornerT<12>(T + T_E, t) - hornerT<12>(T + T_F, t));
+}
+
 // K1(z)/z for z^2 = z2.
 __device__ __forceinline__ double k1z_64(double z2, const double* __restrict__ T) {
-  if (z2 < 4.0) {
-    double t = 0.25 * z2;
-    double lt = log(t);
-    return 0.25 * rcp64(t) + 0.25 * (lt * hornerT<12>(T + T_E, t) - hornerT<12>(T + T_F, t));
-  }
+  if (z2 < 4.0) return k1z_64_small(z2, T);
   double y = rsqrt64(z2);  // 1/z
   double z = z2 * y;
   double q = rsqrt64(z);   // z^(-1/2)
@@ -140,14 +143,20 @@ __device__ __forceinline__ void k0_k1z_64_large(double z2, double& k0, double& k
   k1z = hornerT<NC>(T + H1, s) * e * y;
 }
 
+// K0(z) and K1(z)/z for z^2 = z2 < 4 (the ascending series).
+__device__ __forceinline__ void k0_k1z_64_small(double z2, double& k0, double& k1z,
+                                                const double* __restrict__ T) {
+  double t = 0.25 * z2;
+  double lt = log(t);
+  k0 = -0.5 * lt * hornerT<12>(T + T_I0, t) + hornerT<12>(T + T_P0, t);
+  k1z = 0.25 * rcp64(t) + 0.25 * (lt * hornerT<12>(T + T_E, t) - hornerT<12>(T + T_F, t));
+}
+
 // K0(z) and K1(z)/z together for z^2 = z2.
 __device__ __forceinline__ void k0_k1z_64(double z2, double& k0, double& k1z,
                                           const double* __restrict__ T) {
   if (z2 < 4.0) {
-    double t = 0.25 * z2;
-    double lt = log(t);
-    k0 = -0.5 * lt * hornerT<12>(T + T_I0, t) + hornerT<12>(T + T_P0, t);
-    k1z = 0.25 * rcp64(t) + 0.25 * (lt * hornerT<12>(T + T_E, t) - hornerT<12>(T + T_F, t));
+    k0_k1z_64_small(z2, k0, k1z, T);
     return;
   }
   double y = rsqrt64(z2);
@@ -197,17 +206,24 @@ __device__ inline void bessel_i_series64(double x, int lmax, double* I) {
 // K1(z)/z for z^2 = z2 (> 0, normal).  z < 2: the ascending series with the raw
 // base-2 logarithm (log2 t folded into the coefficients); z >= 2: e^-z z^-3/2
 // h1(2/z) with h1 as a degree-6 polynomial in 1/z.
-__device__ __forceinline__ float k1z_32(float z2) {
-  if (z2 < 4.0f) {
-    const float t = 0.25f * z2;
-    const float l2 = __builtin_amdgcn_logf(t);
-    return fmaf(0.25f, __builtin_amdgcn_rcpf(t), fmaf(l2, horner(kE2_32, t), -horner(kF4_32, t)));
-  }
+// The two branches on their own (the small-z one for z < 2, the other for z >= 2).
+__device__ __forceinline__ float k1z_32_small(float z2) {
+  const float t = 0.25f * z2;
+  const float l2 = __builtin_amdgcn_logf(t);
+  return fmaf(0.25f, __builtin_amdgcn_rcpf(t), fmaf(l2, horner(kE2_32, t), -horner(kF4_32, t)));
+}
+
+__device__ __forceinline__ float k1z_32_large(float z2) {
   const float y = __builtin_amdgcn_rsqf(z2);
   const float z = z2 * y;
   const float e = __builtin_amdgcn_exp2f(-1.4426950408889634f * z);
   const float q = __builtin_amdgcn_rsqf(z);
   return (e * horner(kH1Z_32, y)) * (q * y);
+}
+
+__device__ __forceinline__ float k1z_32(float z2) {
+  if (z2 < 4.0f) return k1z_32_small(z2);
+  return k1z_32_large(z2);
 }
 
 __device__ __forceinline__ void k0_k1z_32(float z2, float& k0, float& k1z) {

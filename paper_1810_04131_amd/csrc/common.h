@@ -172,6 +172,15 @@ __device__ __forceinline__ kptr<T> as_k(const T* p) {
   return (kptr<T>)p;
 }
 
+// A pointer known to address global memory (vector loads with a scalar base and a
+// 32-bit offset instead of generic loads), for pointers read from memory.
+template <class T>
+using gptr = const __attribute__((address_space(1))) T*;
+template <class T>
+__device__ __forceinline__ gptr<T> as_g(const T* p) {
+  return (gptr<T>)p;
+}
+
 // Geometry of one problem as the kernels see it (all device pointers).
 struct GeomView {
   int n;                 // particles

@@ -48,10 +48,21 @@ struct Fmm {
   DevBuf<int> leaf_start, leaf_cnt;   // sorted-node range
   DevBuf<int> leaf_gid;               // box index in Mall / Lall
   DevBuf<double> leaf_cx, leaf_cy;    // box centre
+  DevBuf<double> leaf_r;              // largest distance of a leaf node from the box centre
+  DevBuf<int> leaf_of;                // sorted node -> its leaf
   DevBuf<int> nbp, nbi;               // P2P leaves (CSR, self included): every leaf whose
                                       // ancestor at the coarser of the two levels is adjacent
   int64_t p2p_pairs = 0;              // source-target pairs of one P2P pass
   int64_t m2l_pairs = 0;              // box pairs of one M2L pass
+  // Near-field cache: the leaf pass's pair coefficients K1(z)/z ((x - y) . w nu) for
+  // this geometry, so that the pass reads them instead of evaluating them.  Entry e
+  // of the P2P lists (target leaf b, source leaf nbi[e]) owns the block of
+  // cnt(b) x cnt(nbi[e]) coefficients at blk_off[e], target-fastest.
+  DevBuf<int64_t> blk_off;
+  DevBuf<float> nc32;                 // FP32 coefficients (the inner operator's leaf pass)
+  DevBuf<double> nc64;                // FP64 coefficients (the FP64 leaf pass)
+  int nc_kind = 0;                    // 0 none, 1 FP32, 2 FP64
+  DevBuf<double> ss;                  // the density in sorted node order (cached passes)
   DevBuf<double2> tg;  // M2M / L2L tables: [level][cpos 0..3][k + 2p], k in -2p..2p
   DevBuf<double2> ts;  // M2L tables: [level][offset 0..48][k + 2p]
   int max_leaf = 0;
@@ -105,6 +116,10 @@ struct Fmm {
   void apply_grad(const double* sigma, double* gpart, const double* tab, hipStream_t s);
   void apply(const double* sigma, double* partial, bool p2p_fp32, const double* tab,
              hipStream_t s, const int* stop = nullptr);
+  // computes the near-field cache (FP64 coefficients, else FP32) for the current
+  // geometry; p2p_pairs x 8 (or 4) bytes.  drop_near_cache frees it.
+  void build_near_cache(bool f64, const double* tab, hipStream_t s);
+  void drop_near_cache();
 };
 
 // One tree of an FMM forest as the forest kernels see it (device copy): the
@@ -115,12 +130,18 @@ struct FmmDev {
   int cfg;                 // configuration index in the batch engine
   int depth, nleaf;
   int64_t N, off;          // nodes; offset of the configuration in the batch vectors
+  int64_t p2p_pairs;       // source-target pairs of one leaf pass
+  const int64_t* blk_off;  // near-field cache (nc_kind 1: float, 2: double; 0: none)
+  const void* nc;
+  int nc_kind;
+  double* ss;
   double kappa;
   const int* perm;
   const double *xs, *ys, *wnxs, *wnys;
   double *qx, *qy;
   const int *leaf_start, *leaf_cnt, *leaf_gid, *nbp, *nbi;
-  const double *leaf_cx, *leaf_cy;
+  const double *leaf_cx, *leaf_cy, *leaf_r;
+  const int* leaf_of;
   double2 *Mall, *Lall;
   M2LLevels lv;
   const int* ch[DMAX + 1];

@@ -51,12 +51,25 @@ __device__ __forceinline__ double2 cmad(double2 a, double2 b, double2 c) {
 }
 __device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
 
+// 1/m for m = 1..kRecipN-1, correctly rounded, for the integer reciprocals of the
+// Bessel series and recurrences below (a constant-memory lookup in place of a
+// refined FP64 reciprocal).
+constexpr int kRecipN = 512;
+struct RecipTable {
+  double v[kRecipN];
+  constexpr RecipTable() : v() {
+    for (int m = 1; m < kRecipN; ++m) v[m] = 1.0 / m;
+  }
+};
+__constant__ RecipTable kRecip = RecipTable();
+__device__ __forceinline__ double recip(int m) { return kRecip.v[m]; }
+
 // I_k(x) for one order k by the ascending series, from pref = (x/2)^k / k! and
 // t = x^2 / 4 (all terms positive; reciprocals instead of divisions).
 __device__ __forceinline__ double iorder(double t, double pref, int k) {
   double term = pref, sum = pref;
   for (int j = 1; j < 400; ++j) {
-    term *= t * rcp64(double(j) * double(k + j));
+    term *= t * (recip(j) * recip(k + j));
     sum += term;
     if (term <= 1e-17 * sum) break;
   }
@@ -69,7 +82,7 @@ __device__ inline void iseries(double x, int n, double* I, int stride) {
   double pref = 1.0;
   for (int k = 0; k <= n; ++k) {
     I[(int64_t)k * stride] = iorder(t, pref, k);
-    pref *= 0.5 * x * rcp64(double(k + 1));
+    pref *= 0.5 * x * recip(k + 1);
   }
 }
 
@@ -87,7 +100,7 @@ __device__ inline void iscaled_col(double t, int nmax, double* col) {
   auto ser = [t](int n) {
     double term = 1.0, sum = 1.0;
     for (int k = 1; k < 200; ++k) {
-      term *= t * rcp64(double(k) * double(n + k));
+      term *= t * (recip(k) * recip(n + k));
       sum += term;
       if (term <= 1e-17 * sum) break;
     }
@@ -96,11 +109,48 @@ __device__ inline void iscaled_col(double t, int nmax, double* col) {
   double hi = ser(nmax + 1), cur = ser(nmax);
   col[nmax * 64] = cur;
   for (int n = nmax; n >= 1; --n) {
-    const double prev = fma(t * hi, rcp64(double(n) * double(n + 1)), cur);
+    const double prev = fma(t * hi, recip(n) * recip(n + 1), cur);
     col[(n - 1) * 64] = prev;
     hi = cur;
     cur = prev;
   }
+}
+
+// It_n(x) = I_n(x) n! / (x/2)^n by its ascending series in t = x^2/4.
+__device__ __forceinline__ double iscaled_series(double t, int n) {
+  double term = 1.0, sum = 1.0;
+  for (int k = 1; k < 200; ++k) {
+    term *= t * (recip(k) * recip(n + k));
+    sum += term;
+    if (term <= 1e-17 * sum) break;
+  }
+  return sum;
+}
+
+// The local expansion L_0..L_p of a box with centre (cx, cy) at (xi, yi):
+//   u = L_0 I_0 + 2 Re sum_{n>=1} L_n I_n(x) e^{i n theta},  x = kappa rho,
+// as 2 Re S - L_0 It_0 with S = sum_n L_n It_n z^n / n!, z = (x/2) e^{i theta}: the
+// scaled It_n come down the recurrence of iscaled_col from the series of It_{p+1}
+// and It_p, and S is summed by Horner's rule in the same descending order
+// (registers only, no LDS column).
+__device__ __forceinline__ double l2p_value(double xi, double yi, double cx, double cy,
+                                            double kappa, int p, const double2* __restrict__ lb) {
+  const double dx = xi - cx, dy = yi - cy;
+  const double rho = sqrt(dx * dx + dy * dy);
+  const double x = kappa * rho, t = 0.25 * x * x, hx = 0.5 * x;
+  const double2 e1 = rho > 0.0 ? make_double2(dx / rho, dy / rho) : make_double2(1.0, 0.0);
+  const double2 z = make_double2(hx * e1.x, hx * e1.y);
+  double hi = iscaled_series(t, p + 1), cur = iscaled_series(t, p);
+  double2 R = make_double2(lb[p].x * cur, lb[p].y * cur);
+  for (int n = p; n >= 1; --n) {
+    const double prev = fma(t * hi, recip(n) * recip(n + 1), cur);   // It_{n-1}
+    const double2 Rz = cmul(R, z);
+    const double2 L = lb[n - 1];
+    R = make_double2(fma(L.x, prev, Rz.x * recip(n)), fma(L.y, prev, Rz.y * recip(n)));
+    hi = cur;
+    cur = prev;
+  }
+  return 2.0 * R.x - lb[0].x * cur;
 }
 
 // Sum over the 64 lanes of a wave (fixed butterfly order: the same bits on every run).
@@ -133,7 +183,7 @@ __global__ __launch_bounds__(TAB_BS) void tab_g_kernel(int p, double W, double k
   const double x = kappa * r, tq = 0.25 * x * x;
   for (int k = threadIdx.x; k <= 2 * p; k += TAB_BS) {
     double pref = 1.0;                      // (x/2)^k / k!, built as in iseries
-    for (int j = 0; j < k; ++j) pref *= 0.5 * x * rcp64(double(j + 1));
+    for (int j = 0; j < k; ++j) pref *= 0.5 * x * recip(j + 1);
     I[k] = iorder(tq, pref, k);
   }
   __syncthreads();
@@ -184,22 +234,25 @@ __global__ __launch_bounds__(TAB_BS) void tab_s_kernel(int p, double W, double k
 // ---- per-application kernels -----------------------------------------------------------------
 
 // Sorted node k's source strength w nu sigma (the kernels' q).
+// ss (may be null): the density itself in sorted order (near-field cache passes)
 __device__ __forceinline__ void gather_one(int64_t k, const int* __restrict__ perm,
                                            const double* __restrict__ sigma,
                                            const double* __restrict__ wnxs,
                                            const double* __restrict__ wnys, double* __restrict__ qx,
-                                           double* __restrict__ qy) {
+                                           double* __restrict__ qy, double* __restrict__ ss) {
   const double s = sigma[perm[k]];
   qx[k] = wnxs[k] * s;
   qy[k] = wnys[k] * s;
+  if (ss) ss[k] = s;
 }
 
 __global__ void gather_kernel(int64_t N, const int* __restrict__ perm, const double* __restrict__ sigma,
                               const double* __restrict__ wnxs, const double* __restrict__ wnys,
-                              double* __restrict__ qx, double* __restrict__ qy) {
+                              double* __restrict__ qx, double* __restrict__ qy,
+                              double* __restrict__ ss) {
   const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (k >= N) return;
-  gather_one(k, perm, sigma, wnxs, wnys, qx, qy);
+  gather_one(k, perm, sigma, wnxs, wnys, qx, qy, ss);
 }
 
 constexpr int FB = 64;
@@ -254,7 +307,7 @@ __device__ __forceinline__ void p2m_leaf(int b, int p, int use_col, double kappa
         mine.x += c.x;
         mine.y += c.y;
       }
-      pref *= hx * rcp64(double(n + 2));
+      pref *= hx * recip(n + 2);
       Im = I0;
       I0 = Ip;
       Ip = n + 2 > p + 1 ? 0.0                                 // I_{p+2} is never used
@@ -659,12 +712,13 @@ __global__ void l2l_kernel(int p, int nbox, const int* __restrict__ parent, cons
   Lc[t] = sum;
 }
 
-// Waves per leaf in l2p_p2p_grad_kernel (and l2p_p2p_kernel below kLeavesFor2): wave
+// Waves per leaf in l2p_p2p_grad_kernel (and p2p_kernel below kLeavesFor2): wave
 // w takes every PW-th leaf of the leaf's P2P list (a leaf holds at most leaf_max
 // targets, 64 by default, so one wave per leaf left most SIMDs with a single wave to
-// hide latency); the waves' partial sums are combined in a fixed order by wave 0,
-// which also evaluates the local expansion.  From kLeavesFor2 leaves on the leaves
-// alone fill the SIMDs and l2p_p2p_kernel takes two waves per leaf (measured on the
+// hide latency); the waves' partial sums are combined in a fixed order by wave 0
+// (which in the gradient pass also evaluates the local expansion's gradient).  From
+// kLeavesFor2 leaves on the leaves
+// alone fill the SIMDs and p2p_kernel takes two waves per leaf (measured on the
 // uniform tree this replaced: 4 waves best at 800 leaves, 2 at 4,000; 8 slower at
 // both).
 constexpr int PW = 4;
@@ -677,123 +731,348 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// One block per leaf: local expansion at the leaf's targets plus the direct
-// interactions with the leaves of its P2P list; writes partial[node] in the
-// far-field kernels' scaling (far field * 2 pi / kappa^2).
-// Leaf b; sh: the kernel's dynamic LDS (leaf_lds_bytes).
+// Lane groups of the leaf passes: a round of rem <= 64 targets takes rem lanes per
+// group and G = 64 / rem groups split the sources of every staged tile, so that a
+// leaf of few nodes still keeps most lanes busy.  Lane l serves target l % rem for
+// group l / rem; lanes past G rem read group 0's sources and are not used.
+struct LaneGroups {
+  int rem, G, t, g, ga;
+};
+
+__device__ __forceinline__ LaneGroups lane_groups(int lane, int rem) {
+  LaneGroups r;
+  r.rem = rem;
+  r.G = FB / rem;
+  r.t = lane % rem;
+  r.g = lane / rem;
+  r.ga = r.g < r.G ? r.g : 0;
+  return r;
+}
+
+// Tile slot of the source k of a staged tile of nbk sources for G groups of S =
+// ceil(nbk / G) sources each: group g reads the S consecutive slots from g S.  Slots
+// of k in [nbk, G S) hold padding (zero strength); G S <= nbk + G - 1 < 2 FB.
+__device__ __forceinline__ int group_slot(int k, int G, int S) { return (k % G) * S + k / G; }
+
+// Pair classes of a (target leaf, source leaf) pair from the circles about their box
+// centres that hold their nodes: every z < 2 (the small-z branch of K1(z)/z alone),
+// every z >= 2 (the large-z branch alone), or both kinds (both branches, selected per
+// pair without a branch).  The selection rule is that of k1z_32 / k1z_64 (z^2 < 4).
+constexpr int LC_NEAR = 0, LC_FAR = 1, LC_MIXED = 2;
+
+__device__ __forceinline__ int leaf_class(double kappa, double cx, double cy, double r,
+                                          double sx, double sy, double rs) {
+  const double ex = cx - sx, ey = cy - sy;
+  const double d = sqrt(ex * ex + ey * ey), rr = r + rs;
+  return kappa * (d - rr) >= 2.0 ? LC_FAR : kappa * (d + rr) < 2.0 ? LC_NEAR : LC_MIXED;
+}
+
+template <int CLS>
+__device__ __forceinline__ float leaf_k1z_32(float z2) {
+  if (CLS == LC_NEAR) return k1z_32_small(z2);
+  if (CLS == LC_FAR) return k1z_32_large(z2);
+  const float a = k1z_32_small(z2), b = k1z_32_large(z2);
+  return z2 < 4.0f ? a : b;
+}
+
+template <int CLS>
+__device__ __forceinline__ double leaf_k1z_64(double z2, const double* __restrict__ T) {
+  if (CLS == LC_NEAR) return k1z_64_small(z2, T);
+  if (CLS == LC_FAR) return k1z_64_large<21, T_H1>(z2, T);
+  const double a = k1z_64_small(z2, T), b = k1z_64_large<21, T_H1>(z2, T);
+  return z2 < 4.0 ? a : b;
+}
+
+template <int CLS>
+__device__ __forceinline__ void leaf_k0_k1z_64(double z2, double& k0, double& k1z,
+                                               const double* __restrict__ T) {
+  if (CLS == LC_NEAR) {
+    k0_k1z_64_small(z2, k0, k1z, T);
+  } else if (CLS == LC_FAR) {
+    k0_k1z_64_large<21, T_H0, T_H1>(z2, k0, k1z, T);
+  } else {
+    double a0, a1, b0, b1;
+    k0_k1z_64_small(z2, a0, a1, T);
+    k0_k1z_64_large<21, T_H0, T_H1>(z2, b0, b1, T);
+    const bool sm = z2 < 4.0;
+    k0 = sm ? a0 : b0;
+    k1z = sm ? a1 : b1;
+  }
+}
+
+// The pair sums of far32_tile / far64_tile / far_grad64_tile over nb staged sources
+// for one pair class, with the next source read before the current one is used (the
+// tile has room for one entry past its sources).
+template <int CLS>
+__device__ __forceinline__ float leaf_tile32(double xi, double yi, const double2* sxy,
+                                             const float2* sq, int nb, float kap2, float acc) {
+  double2 p = sxy[0];
+  float2 q = sq[0];
+  for (int k = 0; k < nb; ++k) {
+    const double2 pn = sxy[k + 1];
+    const float2 qn = sq[k + 1];
+    const float dx = (float)(xi - p.x), dy = (float)(yi - p.y);
+    const float z2 = fmaxf(kap2 * fmaf(dx, dx, dy * dy), 1e-30f);
+    acc = fmaf(leaf_k1z_32<CLS>(z2), fmaf(dx, q.x, dy * q.y), acc);
+    p = pn;
+    q = qn;
+  }
+  return acc;
+}
+
+template <int CLS>
+__device__ __forceinline__ double leaf_tile64(double xi, double yi, const double2* sxy,
+                                              const double2* sq, int nb, double kap2,
+                                              const double* __restrict__ tab, double acc) {
+  double2 p = sxy[0], q = sq[0];
+  for (int k = 0; k < nb; ++k) {
+    const double2 pn = sxy[k + 1], qn = sq[k + 1];
+    const double dx = xi - p.x, dy = yi - p.y;
+    const double r2 = fma(dx, dx, dy * dy);
+    const double v = leaf_k1z_64<CLS>(kap2 * r2, tab) * fma(dx, q.x, dy * q.y);
+    acc += r2 > 0.0 ? v : 0.0;
+    p = pn;
+    q = qn;
+  }
+  return acc;
+}
+
+// (the self pair, r = 0, adds nothing; others add exactly far_grad64_tile's terms)
+template <int CLS>
+__device__ __forceinline__ void leaf_grad_tile64(double xi, double yi, const double2* sxy,
+                                                 const double2* sq, int nb, double kap2,
+                                                 const double* __restrict__ tab, double& ax,
+                                                 double& ay) {
+  double2 p = sxy[0], q = sq[0];
+  for (int k = 0; k < nb; ++k) {
+    const double2 pn = sxy[k + 1], qn = sq[k + 1];
+    const double dx = xi - p.x, dy = yi - p.y;
+    const double r2 = fma(dx, dx, dy * dy);
+    const bool self = !(r2 > 0.0);
+    const double r2s = self ? 1.0 : r2;
+    double k0, k1z;
+    leaf_k0_k1z_64<CLS>(kap2 * r2s, k0, k1z, tab);
+    const double dq = fma(dx, q.x, dy * q.y);
+    const double b = dq * (k0 + 2.0 * k1z) * rcp64(r2s);
+    const double gx = k1z * q.x - b * dx, gy = k1z * q.y - b * dy;
+    ax += self ? 0.0 : gx;
+    ay += self ? 0.0 : gy;
+    p = pn;
+    q = qn;
+  }
+}
+
+// LDS of leaf_pass for nw wavefronts: per wavefront a tile of 2 FB positions and
+// 2 FB strengths (FP64, or FP32 in the same space) and FB partial sums.
+static size_t leaf_lds_bytes(int nw) {
+  return (size_t)nw * FB * (4 * sizeof(double2) + sizeof(double));
+}
+
+// LDS of leaf_grad_pass: tiles as above, FB partial gradients per wavefront, columns
+// up to I_{p+1}.
+static size_t leaf_grad_lds_bytes(int p, int use_col) {
+  return (size_t)PW * FB * (4 * sizeof(double2) + sizeof(double2)) +
+         (use_col ? (size_t)(p + 2) * 64 * sizeof(double) : 0);
+}
+
+// One block per leaf: the direct interactions of the leaf's targets with the leaves of
+// its P2P list, added to partial[node] (which holds the local expansion's value from
+// l2p_kernel) in the far-field kernels' scaling (far field * 2 pi / kappa^2).
+// Leaf b; sh: the kernel's dynamic LDS (leaf_lds_bytes); boff, nc, ssd: the
+// near-field cache when nc is set (the coefficients of the pass's precision).
 template <bool F32, int NW>
-__device__ __forceinline__ void leaf_pass(int b, int p, double kappa, int use_local, int use_col,
-                                          const int* __restrict__ ls, const int* __restrict__ lc,
-                                          const int* __restrict__ gid,
+__device__ __forceinline__ void leaf_pass(int b, double kappa, const int* __restrict__ ls,
+                                          const int* __restrict__ lc,
                                           const int* __restrict__ nbp,
                                           const int* __restrict__ nbi,
                                           const double* __restrict__ ccx,
                                           const double* __restrict__ ccy,
-                                          const double2* __restrict__ L,
+                                          const double* __restrict__ lr,
                                           const double* __restrict__ xs,
                                           const double* __restrict__ ys,
                                           const double* __restrict__ qx,
                                           const double* __restrict__ qy,
                                           const int* __restrict__ perm,
                                           const double* __restrict__ tab,
-                                          double* __restrict__ partial, double* sh) {
+                                          double* __restrict__ partial, double* sh,
+                                          const int64_t* __restrict__ boff, const void* nc,
+                                          const double* __restrict__ ssd) {
   // the wave index is uniform over the wave: in a scalar register, the neighbour-leaf
   // and source loops below run on scalar counters (the LDS tiles are addressed from a
   // vector register, so the unrolled pair loop reads them with immediate offsets)
   const int lane = threadIdx.x % FB, w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / FB));
   const int wv = threadIdx.x / FB;
   double2* sbase = reinterpret_cast<double2*>(sh);
-  double2* sxy = sbase + wv * FB;                                       // [NW][FB]
-  double2* sq = sbase + (NW + wv) * FB;                                 // [NW][FB] (FP64)
-  float2* sq32 = reinterpret_cast<float2*>(sbase + 2 * NW * FB) + wv * FB;  // [NW][FB] (FP32)
-  double* red = reinterpret_cast<double*>(reinterpret_cast<float2*>(sbase + 2 * NW * FB) +
-                                          NW * FB);                     // [NW][FB] wave sums
-  double* col = red + NW * FB + lane;   // [(p + 1) * 64] scaled I_n, wave 0
+  double2* sxy = sbase + wv * 2 * FB;                                  // [NW][2 FB]
+  double2* sq = sbase + (NW + wv) * 2 * FB;                            // [NW][2 FB] (FP64)
+  float2* sq32 = reinterpret_cast<float2*>(sq);                        // (FP32, same space)
+  double* red = reinterpret_cast<double*>(sbase + 4 * NW * FB);        // [NW][FB] wave sums
   const int s0 = ls[b], cnt = lc[b];
   const double kap2 = kappa * kappa;
   const double cx = ccx[b], cy = ccy[b];
   for (int r0 = 0; r0 < cnt; r0 += FB) {
-    const int j = r0 + lane;
-    const bool act = j < cnt;
-    const double xi = act ? xs[s0 + j] : cx, yi = act ? ys[s0 + j] : cy;
+    const LaneGroups lg = lane_groups(lane, min(cnt - r0, FB));
+    const int j = r0 + lg.t;
+    const double xi = xs[s0 + j], yi = ys[s0 + j];
+    const bool act = lg.g == 0;   // one lane per target: the sums of every wave and group
     double acc64 = 0.0;
     float acc32 = 0.0f;
     for (int e = nbp[b] + w; e < nbp[b + 1]; e += NW) {
       const int nb = __builtin_amdgcn_readfirstlane(nbi[e]);
       const int t0 = __builtin_amdgcn_readfirstlane(ls[nb]);
       const int tc = __builtin_amdgcn_readfirstlane(lc[nb]);
+      if (nc) {
+        // cached coefficients: group g takes the sources [g S, g S + S) of the block,
+        // CB at a time with every load issued before the first use (the pass is bound
+        // by the loads in flight)
+        constexpr int CB = 8;
+        const int64_t bo = boff[e];
+        const gptr<float> cb32 = as_g(static_cast<const float*>(nc) + bo);
+        const gptr<double> cb64 = as_g(static_cast<const double*>(nc) + bo);
+        const gptr<double> sb = as_g(ssd + t0);
+        const int S = (tc + lg.G - 1) / lg.G, k0 = lg.ga * S;
+        const int kend = min(k0 + S, tc);   // this group's sources end here
+        for (int u = 0; u < S; u += CB) {
+          float c32[CB];
+          double c64[CB], sv[CB];
+#pragma unroll
+          for (int v = 0; v < CB; ++v) {
+            const int kc = min(k0 + u + v, tc - 1);
+            const int a = kc * cnt + j;   // within the block (< 2^31)
+            if (F32)
+              c32[v] = cb32[a];
+            else
+              c64[v] = cb64[a];
+            sv[v] = sb[kc];
+          }
+#pragma unroll
+          for (int v = 0; v < CB; ++v) {
+            const bool ok = k0 + u + v < kend;
+            if (F32)
+              acc32 = fmaf(ok ? c32[v] : 0.0f, (float)sv[v], acc32);
+            else
+              acc64 = fma(ok ? c64[v] : 0.0, sv[v], acc64);
+          }
+        }
+        continue;
+      }
+      const int cls = leaf_class(kappa, cx, cy, lr[b], ccx[nb], ccy[nb], lr[nb]);
       for (int k0 = 0; k0 < tc; k0 += FB) {
+        const int nbk = min(FB, tc - k0);
+        const int S = (nbk + lg.G - 1) / lg.G;
         wave_sync();   // this wave's reads of the previous tile are done
-        if (k0 + lane < tc) {
-          const int k = t0 + k0 + lane;
-          sxy[lane] = make_double2(xs[k], ys[k]);
-          if (F32)
-            sq32[lane] = make_float2((float)qx[k], (float)qy[k]);
-          else
-            sq[lane] = make_double2(qx[k], qy[k]);
+        for (int k = lane; k < lg.G * S; k += FB) {
+          const int sl = group_slot(k, lg.G, S);
+          if (k < nbk) {
+            const int ks = t0 + k0 + k;
+            sxy[sl] = make_double2(as_g(xs)[ks], as_g(ys)[ks]);
+            if (F32)
+              sq32[sl] = make_float2((float)as_g(qx)[ks], (float)as_g(qy)[ks]);
+            else
+              sq[sl] = make_double2(as_g(qx)[ks], as_g(qy)[ks]);
+          } else {   // padding: zero strength at a point of no target
+            sxy[sl] = make_double2(cx + 1.0, cy);
+            if (F32)
+              sq32[sl] = make_float2(0.0f, 0.0f);
+            else
+              sq[sl] = make_double2(0.0, 0.0);
+          }
         }
         wave_sync();
-        const int nbk = min(FB, tc - k0);
-        if (F32)
-          acc32 = far32_tile(xi, yi, sxy, sq32, nbk, (float)kap2, acc32);
-        else
-          acc64 = far64_tile(xi, yi, sxy, sq, nbk, kap2, tab, acc64);
+        const int g0 = lg.ga * S;
+        if (F32) {
+          const float k2 = (float)kap2;
+          if (cls == LC_NEAR)
+            acc32 = leaf_tile32<LC_NEAR>(xi, yi, sxy + g0, sq32 + g0, S, k2, acc32);
+          else if (cls == LC_FAR)
+            acc32 = leaf_tile32<LC_FAR>(xi, yi, sxy + g0, sq32 + g0, S, k2, acc32);
+          else
+            acc32 = leaf_tile32<LC_MIXED>(xi, yi, sxy + g0, sq32 + g0, S, k2, acc32);
+        } else {
+          if (cls == LC_NEAR)
+            acc64 = leaf_tile64<LC_NEAR>(xi, yi, sxy + g0, sq + g0, S, kap2, tab, acc64);
+          else if (cls == LC_FAR)
+            acc64 = leaf_tile64<LC_FAR>(xi, yi, sxy + g0, sq + g0, S, kap2, tab, acc64);
+          else
+            acc64 = leaf_tile64<LC_MIXED>(xi, yi, sxy + g0, sq + g0, S, kap2, tab, acc64);
+        }
       }
     }
     red[w * FB + lane] = F32 ? (double)acc32 : acc64;
     __syncthreads();
-    if (w == 0) {
-      double direct = red[lane];
-      for (int q = 1; q < NW; ++q) direct += red[q * FB + lane];
-      double loc = 0.0;
-      if (use_local && act) {
-        const double dx = xi - cx, dy = yi - cy;
-        const double rho = sqrt(dx * dx + dy * dy);
-        const double x = kappa * rho, t = 0.25 * x * x, hx = 0.5 * x;
-        const double2 e1 = rho > 0.0 ? make_double2(dx / rho, dy / rho) : make_double2(1.0, 0.0);
-        const double2* lb = L + (int64_t)gid[b] * (p + 1);
-        if (use_col) iscaled_col(t, p, col);
-        loc = lb[0].x * (use_col ? col[0] : iorder(t, 1.0, 0));
-        double2 E = e1;
-        double pref = 1.0;                      // (x/2)^n / n!
-        for (int n = 1; n <= p; ++n) {
-          pref *= hx * rcp64(double(n));
-          const double2 v = cmul(lb[n], E);
-          loc += 2.0 * v.x * (use_col ? pref * col[n * 64] : iorder(t, pref, n));
-          E = cmul(E, e1);
-        }
-      }
-      if (act) partial[perm[s0 + j]] = direct + loc * (2.0 * PI / kap2);
+    if (w == 0 && act) {
+      double direct = 0.0;
+      for (int q = 0; q < NW; ++q)
+        for (int gg = 0; gg < lg.G; ++gg) direct += red[q * FB + gg * lg.rem + lg.t];
+      // the local expansion's value is there already (l2p_kernel)
+      const int node = perm[s0 + j];
+      partial[node] = partial[node] + direct;
     }
     __syncthreads();   // red is rewritten by the next group of targets
   }
 }
 
 template <bool F32, int NW>
-__global__ __launch_bounds__(FB * NW) void l2p_p2p_kernel(int p, double kappa, int use_local, int use_col,
-                                                          const int* __restrict__ ls,
-                                                          const int* __restrict__ lc,
-                                                          const int* __restrict__ gid,
-                                                          const int* __restrict__ nbp,
-                                                          const int* __restrict__ nbi,
-                                                          const double* __restrict__ ccx,
-                                                          const double* __restrict__ ccy,
-                                                          const double2* __restrict__ L,
-                                                          const double* __restrict__ xs,
-                                                          const double* __restrict__ ys,
-                                                          const double* __restrict__ qx,
-                                                          const double* __restrict__ qy,
-                                                          const int* __restrict__ perm,
-                                                          const double* __restrict__ tab,
-                                                          double* __restrict__ partial,
-                                                          const int* __restrict__ stop) {
+__global__ __launch_bounds__(FB * NW) void p2p_kernel(double kappa, const int* __restrict__ ls,
+                                                      const int* __restrict__ lc,
+                                                      const int* __restrict__ nbp,
+                                                      const int* __restrict__ nbi,
+                                                      const double* __restrict__ ccx,
+                                                      const double* __restrict__ ccy,
+                                                      const double* __restrict__ lr,
+                                                      const double* __restrict__ xs,
+                                                      const double* __restrict__ ys,
+                                                      const double* __restrict__ qx,
+                                                      const double* __restrict__ qy,
+                                                      const int* __restrict__ perm,
+                                                      const double* __restrict__ tab,
+                                                      double* __restrict__ partial,
+                                                      const int* __restrict__ stop,
+                                                      const int64_t* __restrict__ boff,
+                                                      const void* nc,
+                                                      const double* __restrict__ ssd) {
   if (stop && *stop) return;
   extern __shared__ double sh[];
-  leaf_pass<F32, NW>(blockIdx.x, p, kappa, use_local, use_col, ls, lc, gid, nbp, nbi, ccx, ccy, L,
-                     xs, ys, qx, qy, perm, tab, partial, sh);
+  leaf_pass<F32, NW>(blockIdx.x, kappa, ls, lc, nbp, nbi, ccx, ccy, lr, xs, ys, qx, qy, perm, tab,
+                     partial, sh, boff, nc, ssd);
 }
 
-// Gradient counterpart of l2p_p2p_kernel (FP64): the direct gradient from the
+// The local expansion's value at sorted node k of a tree (leaf leaf_of[k]):
+// partial[perm[k]] = (2 pi / kappa^2) u_local, one node per thread.
+__device__ __forceinline__ void l2p_node(int64_t k, int p, double kappa,
+                                         const int* __restrict__ leaf_of,
+                                         const int* __restrict__ gid,
+                                         const double* __restrict__ ccx,
+                                         const double* __restrict__ ccy,
+                                         const double* __restrict__ xs,
+                                         const double* __restrict__ ys,
+                                         const int* __restrict__ perm,
+                                         const double2* __restrict__ L,
+                                         double* __restrict__ partial) {
+  const int b = leaf_of[k];
+  const double u = l2p_value(xs[k], ys[k], ccx[b], ccy[b], kappa, p,
+                             L + (int64_t)gid[b] * (p + 1));
+  partial[perm[k]] = u * (2.0 * PI / (kappa * kappa));
+}
+
+__global__ __launch_bounds__(256) void l2p_kernel(int64_t N, int p, double kappa,
+                                                  const int* __restrict__ leaf_of,
+                                                  const int* __restrict__ gid,
+                                                  const double* __restrict__ ccx,
+                                                  const double* __restrict__ ccy,
+                                                  const double* __restrict__ xs,
+                                                  const double* __restrict__ ys,
+                                                  const int* __restrict__ perm,
+                                                  const double2* __restrict__ L,
+                                                  double* __restrict__ partial,
+                                                  const int* __restrict__ stop) {
+  if (stop && *stop) return;
+  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k >= N) return;
+  l2p_node(k, p, kappa, leaf_of, gid, ccx, ccy, xs, ys, perm, L, partial);
+}
+
+// Gradient counterpart of l2p_kernel + p2p_kernel (FP64): the direct gradient from the
 // leaves of the P2P list plus the local expansion's gradient
 //   u_x + i u_y = kappa [ L_0 I_1 e^{i theta}
 //                 + sum_{n>=1} (L_n I_{n+1} e^{i(n+1) theta} + conj(L_n) I_{n-1} e^{-i(n-1) theta}) ],
@@ -809,6 +1088,7 @@ __device__ __forceinline__ void leaf_grad_pass(int b, int p, int use_col, double
                                                const int* __restrict__ nbi,
                                                const double* __restrict__ ccx,
                                                const double* __restrict__ ccy,
+                                               const double* __restrict__ lr,
                                                const double2* __restrict__ L,
                                                const double* __restrict__ xs,
                                                const double* __restrict__ ys,
@@ -817,45 +1097,65 @@ __device__ __forceinline__ void leaf_grad_pass(int b, int p, int use_col, double
                                                const int* __restrict__ perm, int64_t N,
                                                const double* __restrict__ tab,
                                                double* __restrict__ gpart, double* sh) {
-  // the neighbour leaves are split over PW wavefronts as in l2p_p2p_kernel
+  // the neighbour leaves are split over PW wavefronts as in p2p_kernel
   // the wave index is uniform over the wave: in a scalar register, the neighbour-leaf
   // and source loops below run on scalar counters
   const int lane = threadIdx.x % FB, w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / FB));
+  const int wv = threadIdx.x / FB;
   double2* sbase = reinterpret_cast<double2*>(sh);
-  double2* sxy = sbase + w * FB;                              // [PW][FB]
-  double2* sq = sbase + (PW + w) * FB;                        // [PW][FB]
-  double2* red = sbase + 2 * PW * FB;                         // [PW][FB] wave sums (x, y)
+  double2* sxy = sbase + wv * 2 * FB;                          // [PW][2 FB]
+  double2* sq = sbase + (PW + wv) * 2 * FB;                    // [PW][2 FB]
+  double2* red = sbase + 4 * PW * FB;                          // [PW][FB] wave sums (x, y)
   double* col = reinterpret_cast<double*>(red + PW * FB) + lane;   // [(p + 2) * 64] scaled I_n
   const int s0 = ls[b], cnt = lc[b];
   const double kap2 = kappa * kappa;
   const double cx = ccx[b], cy = ccy[b];
   for (int r0 = 0; r0 < cnt; r0 += FB) {
-    const int j = r0 + lane;
-    const bool act = j < cnt;
-    const double xi = act ? xs[s0 + j] : cx, yi = act ? ys[s0 + j] : cy;
+    const LaneGroups lg = lane_groups(lane, min(cnt - r0, FB));
+    const int j = r0 + lg.t;
+    const double xi = xs[s0 + j], yi = ys[s0 + j];
     double ax = 0.0, ay = 0.0;
     for (int e = nbp[b] + w; e < nbp[b + 1]; e += PW) {
       const int nb = __builtin_amdgcn_readfirstlane(nbi[e]);
       const int t0 = __builtin_amdgcn_readfirstlane(ls[nb]);
       const int tc = __builtin_amdgcn_readfirstlane(lc[nb]);
+      const int cls = leaf_class(kappa, cx, cy, lr[b], ccx[nb], ccy[nb], lr[nb]);
       for (int k0 = 0; k0 < tc; k0 += FB) {
+        const int nbk = min(FB, tc - k0);
+        const int S = (nbk + lg.G - 1) / lg.G;
         wave_sync();   // this wave's reads of the previous tile are done
-        if (k0 + lane < tc) {
-          const int k = t0 + k0 + lane;
-          sxy[lane] = make_double2(xs[k], ys[k]);
-          sq[lane] = make_double2(qx[k], qy[k]);
+        for (int k = lane; k < lg.G * S; k += FB) {
+          const int sl = group_slot(k, lg.G, S);
+          if (k < nbk) {
+            const int ks = t0 + k0 + k;
+            sxy[sl] = make_double2(as_g(xs)[ks], as_g(ys)[ks]);
+            sq[sl] = make_double2(as_g(qx)[ks], as_g(qy)[ks]);
+          } else {   // padding: zero strength at a point of no target
+            sxy[sl] = make_double2(cx + 1.0, cy);
+            sq[sl] = make_double2(0.0, 0.0);
+          }
         }
         wave_sync();
-        far_grad64_tile(xi, yi, sxy, sq, min(FB, tc - k0), kap2, tab, ax, ay);
+        const int g0 = lg.ga * S;
+        if (cls == LC_NEAR)
+          leaf_grad_tile64<LC_NEAR>(xi, yi, sxy + g0, sq + g0, S, kap2, tab, ax, ay);
+        else if (cls == LC_FAR)
+          leaf_grad_tile64<LC_FAR>(xi, yi, sxy + g0, sq + g0, S, kap2, tab, ax, ay);
+        else
+          leaf_grad_tile64<LC_MIXED>(xi, yi, sxy + g0, sq + g0, S, kap2, tab, ax, ay);
       }
     }
     red[w * FB + lane] = make_double2(ax, ay);
     __syncthreads();
-    if (w == 0) {
-      for (int q = 1; q < PW; ++q) {
-        ax += red[q * FB + lane].x;
-        ay += red[q * FB + lane].y;
-      }
+    const bool act = lg.g == 0;   // one lane per target: the sums of every wave and group
+    if (w == 0 && act) {
+      ax = 0.0;
+      ay = 0.0;
+      for (int q = 0; q < PW; ++q)
+        for (int gg = 0; gg < lg.G; ++gg) {
+          ax += red[q * FB + gg * lg.rem + lg.t].x;
+          ay += red[q * FB + gg * lg.rem + lg.t].y;
+        }
     }
     if (w == 0 && act) {
       const double dx = xi - cx, dy = yi - cy;
@@ -871,7 +1171,7 @@ __device__ __forceinline__ void leaf_grad_pass(int b, int p, int use_col, double
       double2 Eprev = make_double2(1.0, 0.0);             // e^{i(n-1) theta}
       double2 Enext = e1;                                 // e^{i(n+1) theta} after the update
       for (int n = 1; n <= p; ++n) {
-        pref *= hx * rcp64(double(n + 1));
+        pref *= hx * recip(n + 1);
         const double Inext = use_col ? pref * col[(n + 1) * 64] : iorder(t, pref, n + 1);
         Enext = cmul(Enext, e1);
         const double2 a = cmul(lb[n], Enext);
@@ -899,6 +1199,7 @@ __global__ __launch_bounds__(FB * PW) void l2p_p2p_grad_kernel(int p, int use_co
                                                           const int* __restrict__ nbi,
                                                           const double* __restrict__ ccx,
                                                           const double* __restrict__ ccy,
+                                                          const double* __restrict__ lr,
                                                           const double2* __restrict__ L,
                                                           const double* __restrict__ xs,
                                                           const double* __restrict__ ys,
@@ -908,8 +1209,8 @@ __global__ __launch_bounds__(FB * PW) void l2p_p2p_grad_kernel(int p, int use_co
                                                           const double* __restrict__ tab,
                                                           double* __restrict__ gpart) {
   extern __shared__ double sh[];
-  leaf_grad_pass(blockIdx.x, p, use_col, kappa, ls, lc, gid, nbp, nbi, ccx, ccy, L, xs, ys, qx, qy,
-                 perm, N, tab, gpart, sh);
+  leaf_grad_pass(blockIdx.x, p, use_col, kappa, ls, lc, gid, nbp, nbi, ccx, ccy, lr, L, xs, ys, qx,
+                 qy, perm, N, tab, gpart, sh);
 }
 
 // ---- tree keys (device) ------------------------------------------------------------------
@@ -979,6 +1280,22 @@ __global__ void keys_kernel(const double* __restrict__ x, const double* __restri
 }
 
 // Sorted copies of positions and w nu (perm: sorted position -> node).
+// r[b] = the largest distance of leaf b's nodes from its box centre (with a relative
+// margin far above rounding), for the leaf passes' pair classes.
+__global__ void leaf_radius_kernel(int nleaf, const int* __restrict__ ls,
+                                   const int* __restrict__ lc, const double* __restrict__ ccx,
+                                   const double* __restrict__ ccy, const double* __restrict__ xs,
+                                   const double* __restrict__ ys, double* __restrict__ r) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nleaf) return;
+  double m = 0.0;
+  for (int k = ls[b]; k < ls[b] + lc[b]; ++k) {
+    const double dx = xs[k] - ccx[b], dy = ys[k] - ccy[b];
+    m = fmax(m, sqrt(dx * dx + dy * dy));
+  }
+  r[b] = m * (1.0 + 1e-12);
+}
+
 __global__ void sort_gather_kernel(int64_t n, const int* __restrict__ perm,
                                    const double* __restrict__ x, const double* __restrict__ y,
                                    const double* __restrict__ wx, const double* __restrict__ wy,
@@ -1192,14 +1509,36 @@ void Fmm::build(int64_t n, double kap, int order, int lmax, const double* tab, h
   }
   up(leaf_start, t.leaf_start);
   up(leaf_cnt, t.leaf_cnt);
+  {
+    std::vector<int> lo(n);
+    for (int k = 0; k < nleaf; ++k)
+      for (int q = 0; q < t.leaf_cnt[k]; ++q) lo[t.leaf_start[k] + q] = k;
+    up(leaf_of, lo);
+  }
   up(leaf_gid, gid);
   up(leaf_cx, lcx);
   up(leaf_cy, lcy);
   up(nbp, t.nbp);
   up(nbi, t.nbi);
+  {
+    std::vector<int64_t> bo(t.nbi.size());
+    int64_t acc = 0;
+    for (int k = 0; k < nleaf; ++k)
+      for (int e = t.nbp[k]; e < t.nbp[k + 1]; ++e) {
+        bo[e] = acc;
+        acc += (int64_t)t.leaf_cnt[k] * t.leaf_cnt[t.nbi[e]];
+      }
+    up(blk_off, bo);
+  }
+  drop_near_cache();   // coefficients of the previous geometry
   qx.fit(n);
   qy.fit(n);
   up.finish();
+  leaf_r.fit(std::max(nleaf, 1));
+  leaf_radius_kernel<<<(nleaf + 255) / 256, 256, 0, s>>>(nleaf, leaf_start.p, leaf_cnt.p,
+                                                          leaf_cx.p, leaf_cy.p, xs.p, ys.p,
+                                                          leaf_r.p);
+  YQ_HIP(hipGetLastError());
   set_order(order, tab, s);
 }
 
@@ -1261,6 +1600,7 @@ void Fmm::set_order(int q, const double* tab, hipStream_t s) {
 
 // A second expansion order on the same tree: copies the tree (device to device).
 void Fmm::copy_tree(const Fmm& o, int q, const double* tab, hipStream_t s) {
+  drop_near_cache();   // coefficients of the previous geometry
   // the device-to-device copies go in one batch_copy_kernel launch
   std::vector<CopyItem> cp;
   auto dup = [&](auto& dst, const auto& src) {
@@ -1308,6 +1648,9 @@ void Fmm::copy_tree(const Fmm& o, int q, const double* tab, hipStream_t s) {
   dup(leaf_gid, o.leaf_gid);
   dup(leaf_cx, o.leaf_cx);
   dup(leaf_cy, o.leaf_cy);
+  dup(leaf_r, o.leaf_r);
+  dup(blk_off, o.blk_off);
+  dup(leaf_of, o.leaf_of);
   dup(nbp, o.nbp);
   dup(nbi, o.nbi);
   if (!cp.empty()) {
@@ -1405,7 +1748,7 @@ void Fmm::expansions(const double* sigma, hipStream_t s, bool m2l32, const int* 
   YQ_REQUIRE(built, YQ_ESTATE, "FMM tree not built");
   const int K = 4 * p + 1;
   gather_kernel<<<(unsigned)((N + 255) / 256), 256, 0, s>>>(N, perm.p, sigma, wnxs.p, wnys.p, qx.p,
-                                                            qy.p);
+                                                            qy.p, nc_kind ? ss.p : nullptr);
   const int col = p <= kColMaxOrder;
   p2m_kernel<<<nleaf, 64, col ? (size_t)(p + 2) * 64 * sizeof(double) : 0, s>>>(
       p, col, kappa, leaf_start.p, leaf_cnt.p, leaf_gid.p, leaf_cx.p, leaf_cy.p, xs.p, ys.p, qx.p,
@@ -1449,27 +1792,96 @@ void Fmm::apply(const double* sigma, double* partial, bool p2p_fp32, const doubl
                 hipStream_t s, const int* stop) {
   // the FP32-class (inner) operator also takes its M2L in FP32 when that is set up
   expansions(sigma, s, p2p_fp32 && want_m2l32 && use_mfma, stop);
-  const int col = p <= kColMaxOrder;
+  l2p_kernel<<<(unsigned)((N + 255) / 256), 256, 0, s>>>(N, p, kappa, leaf_of.p, leaf_gid.p,
+                                                         leaf_cx.p, leaf_cy.p, xs.p, ys.p, perm.p,
+                                                         Lall.p, partial, stop);
   const int nw = nleaf >= kLeavesFor2 ? 2 : PW;
-  const size_t sh_l = (size_t)nw * FB * (2 * sizeof(double2) + sizeof(float2) + sizeof(double)) +
-                      (col ? (size_t)(p + 1) * 64 * sizeof(double) : 0);
-  auto k = p2p_fp32 ? (nw == 2 ? l2p_p2p_kernel<true, 2> : l2p_p2p_kernel<true, PW>)
-                    : (nw == 2 ? l2p_p2p_kernel<false, 2> : l2p_p2p_kernel<false, PW>);
-  k<<<nleaf, FB * nw, sh_l, s>>>(p, kappa, 1, col, leaf_start.p, leaf_cnt.p, leaf_gid.p, nbp.p,
-                                 nbi.p, leaf_cx.p, leaf_cy.p, Lall.p, xs.p, ys.p, qx.p, qy.p,
-                                 perm.p, tab, partial, stop);
+  // the near-field cache of the apply's precision, if computed
+  const void* cache = p2p_fp32 ? (nc_kind == 1 ? (const void*)nc32.p : nullptr)
+                               : (nc_kind == 2 ? (const void*)nc64.p : nullptr);
+  auto k = p2p_fp32 ? (nw == 2 ? p2p_kernel<true, 2> : p2p_kernel<true, PW>)
+                    : (nw == 2 ? p2p_kernel<false, 2> : p2p_kernel<false, PW>);
+  k<<<nleaf, FB * nw, leaf_lds_bytes(nw), s>>>(kappa, leaf_start.p, leaf_cnt.p, nbp.p, nbi.p,
+                                               leaf_cx.p, leaf_cy.p, leaf_r.p, xs.p, ys.p, qx.p,
+                                               qy.p, perm.p, tab, partial, stop, blk_off.p,
+                                               cache, cache ? ss.p : nullptr);
   YQ_HIP(hipGetLastError());
+}
+
+// Near-field cache: one wave per leaf computes the coefficients of every pair of its
+// P2P list with the leaf passes' arithmetic (FP64: far64_tile's terms, the self
+// pair 0; FP32: far32_tile's, positions differenced in FP64) without the density:
+// K1(z)/z ((x_i - y_k) . w_k nu_k) at boff[e] + k cnt + i.
+template <bool F64>
+__global__ __launch_bounds__(64) void near_cache_kernel(
+    const int* __restrict__ ls, const int* __restrict__ lc, const int* __restrict__ nbp,
+    const int* __restrict__ nbi, const int64_t* __restrict__ boff, const double* __restrict__ xs,
+    const double* __restrict__ ys, const double* __restrict__ wnxs,
+    const double* __restrict__ wnys, double kappa, const double* __restrict__ tab, void* out) {
+  const int b = blockIdx.x, lane = threadIdx.x;
+  const int s0 = ls[b], cnt = lc[b];
+  const double kap2 = kappa * kappa;
+  for (int r0 = 0; r0 < cnt; r0 += 64) {
+    const int i = r0 + lane;
+    const bool act = i < cnt;
+    const double xi = act ? xs[s0 + i] : 0.0, yi = act ? ys[s0 + i] : 0.0;
+    for (int e = nbp[b]; e < nbp[b + 1]; ++e) {
+      const int nb = nbi[e];
+      const int t0 = ls[nb], tc = lc[nb];
+      const int64_t bo = boff[e];
+      for (int k = 0; k < tc; ++k) {
+        const double xk = xs[t0 + k], yk = ys[t0 + k], wx = wnxs[t0 + k], wy = wnys[t0 + k];
+        if (F64) {
+          const double dx = xi - xk, dy = yi - yk;
+          const double r2 = fma(dx, dx, dy * dy);
+          const double v = k1z_64(kap2 * r2, tab) * fma(dx, wx, dy * wy);
+          if (act) static_cast<double*>(out)[bo + (int64_t)k * cnt + i] = r2 > 0.0 ? v : 0.0;
+        } else {
+          const float dx = (float)(xi - xk), dy = (float)(yi - yk);
+          const float z2 = fmaxf((float)kap2 * fmaf(dx, dx, dy * dy), 1e-30f);
+          const float v = k1z_32(z2) * fmaf(dx, (float)wx, dy * (float)wy);
+          if (act) static_cast<float*>(out)[bo + (int64_t)k * cnt + i] = v;
+        }
+      }
+    }
+  }
+}
+
+void Fmm::build_near_cache(bool f64, const double* tab, hipStream_t s) {
+  YQ_REQUIRE(nleaf > 0 && blk_off.p, YQ_ESTATE, "FMM tree not built");
+  drop_near_cache();
+  const size_t np = (size_t)std::max<int64_t>(p2p_pairs, 1);
+  void* out;
+  if (f64) {
+    nc64.fit(np);
+    out = nc64.p;
+  } else {
+    nc32.fit(np);
+    out = nc32.p;
+  }
+  ss.fit(std::max<int64_t>(N, 1));
+  auto k = f64 ? near_cache_kernel<true> : near_cache_kernel<false>;
+  k<<<nleaf, 64, 0, s>>>(leaf_start.p, leaf_cnt.p, nbp.p, nbi.p, blk_off.p, xs.p, ys.p, wnxs.p,
+                         wnys.p, kappa, tab, out);
+  YQ_HIP(hipGetLastError());
+  nc_kind = f64 ? 2 : 1;
+}
+
+void Fmm::drop_near_cache() {
+  nc32.release();
+  nc64.release();
+  ss.release();
+  nc_kind = 0;
 }
 
 void Fmm::apply_grad(const double* sigma, double* gpart, const double* tab, hipStream_t s) {
   expansions(sigma, s);
   const int col = p <= kColMaxOrder;
-  const size_t sh =
-      (size_t)PW * FB * 3 * sizeof(double2) + (col ? (size_t)(p + 2) * 64 * sizeof(double) : 0);
+  const size_t sh = leaf_grad_lds_bytes(p, col);
   l2p_p2p_grad_kernel<<<nleaf, FB * PW, sh, s>>>(p, col, kappa, leaf_start.p, leaf_cnt.p,
                                                   leaf_gid.p, nbp.p, nbi.p, leaf_cx.p, leaf_cy.p,
-                                                  Lall.p, xs.p, ys.p, qx.p, qy.p, perm.p, N, tab,
-                                                  gpart);
+                                                  leaf_r.p, Lall.p, xs.p, ys.p, qx.p, qy.p, perm.p,
+                                                  N, tab, gpart);
   YQ_HIP(hipGetLastError());
 }
 
@@ -1488,7 +1900,7 @@ __global__ void forest_gather_kernel(const FmmDev* __restrict__ fd, const int2* 
   const int64_t k = (int64_t)it.y * 256 + threadIdx.x;
   if (k >= d.N) return;
   const double* sigma = V + (col ? (int64_t)col[d.cfg] * T : 0) + d.off;
-  gather_one(k, d.perm, sigma, d.wnxs, d.wnys, d.qx, d.qy);
+  gather_one(k, d.perm, sigma, d.wnxs, d.wnys, d.qx, d.qy, d.ss);
 }
 
 __global__ __launch_bounds__(64) void forest_p2m_kernel(const FmmDev* __restrict__ fd,
@@ -1547,21 +1959,46 @@ __global__ __launch_bounds__(256) void forest_m2l_kernel(const FmmDev* __restric
 template <bool F32, int NW>
 __global__ __launch_bounds__(FB * NW) void forest_leaf_kernel(const FmmDev* __restrict__ fd,
                                                               const int2* __restrict__ items,
-                                                              const int* __restrict__ mask, int p,
-                                                              int use_col,
-                                                              unsigned long long* __restrict__ pairs) {
+                                                              const int* __restrict__ mask) {
   extern __shared__ double sh[];
   const int2 it = items[blockIdx.x];
   const FmmDev& d = fd[it.x];
   if (!mask[d.cfg]) return;
-  if (pairs && threadIdx.x == 0) {   // profiling: targets x the sources of the leaf's P2P list
-    unsigned long long ns = 0;
-    for (int e = d.nbp[it.y]; e < d.nbp[it.y + 1]; ++e) ns += (unsigned long long)d.leaf_cnt[d.nbi[e]];
-    atomicAdd(pairs, ns * (unsigned long long)d.leaf_cnt[it.y]);
+  leaf_pass<F32, NW>(it.y, d.kappa, d.leaf_start, d.leaf_cnt, d.nbp, d.nbi, d.leaf_cx, d.leaf_cy,
+                     d.leaf_r, d.xs, d.ys, d.qx, d.qy, d.perm, d.tab, d.out, sh, d.blk_off, d.nc,
+                     d.ss);
+}
+
+// l2p_kernel over the forest: items (member, 256-node block of its sorted nodes).
+__global__ __launch_bounds__(256) void forest_l2p_kernel(const FmmDev* __restrict__ fd,
+                                                         const int2* __restrict__ items,
+                                                         const int* __restrict__ mask, int p) {
+  const int2 it = items[blockIdx.x];
+  const FmmDev& d = fd[it.x];
+  if (!mask[d.cfg]) return;
+  const int64_t k = (int64_t)it.y * 256 + threadIdx.x;
+  if (k >= d.N) return;
+  l2p_node(k, p, d.kappa, d.leaf_of, d.leaf_gid, d.leaf_cx, d.leaf_cy, d.xs, d.ys, d.perm, d.Lall,
+           d.out);
+}
+
+// Profiling: adds the source-target pairs of the leaf passes of the trees in mask
+// (each tree's count from its build) to *pairs.
+__global__ __launch_bounds__(256) void forest_count_pairs_kernel(const FmmDev* __restrict__ fd,
+                                                                 int nmem,
+                                                                 const int* __restrict__ mask,
+                                                                 unsigned long long* __restrict__ pairs) {
+  __shared__ unsigned long long part[256];
+  unsigned long long s = 0;
+  for (int m = threadIdx.x; m < nmem; m += blockDim.x)
+    if (mask[fd[m].cfg]) s += (unsigned long long)fd[m].p2p_pairs;
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
+    __syncthreads();
   }
-  leaf_pass<F32, NW>(it.y, p, d.kappa, 1, use_col, d.leaf_start, d.leaf_cnt, d.leaf_gid, d.nbp,
-                     d.nbi, d.leaf_cx, d.leaf_cy, d.Lall, d.xs, d.ys, d.qx, d.qy, d.perm, d.tab,
-                     d.out, sh);
+  if (threadIdx.x == 0) atomicAdd(pairs, part[0]);
 }
 
 __global__ __launch_bounds__(FB * PW) void forest_leaf_grad_kernel(const FmmDev* __restrict__ fd,
@@ -1573,21 +2010,12 @@ __global__ __launch_bounds__(FB * PW) void forest_leaf_grad_kernel(const FmmDev*
   const FmmDev& d = fd[it.x];
   if (!mask[d.cfg]) return;
   leaf_grad_pass(it.y, p, use_col, d.kappa, d.leaf_start, d.leaf_cnt, d.leaf_gid, d.nbp, d.nbi,
-                 d.leaf_cx, d.leaf_cy, d.Lall, d.xs, d.ys, d.qx, d.qy, d.perm, d.N, d.tab, d.gout,
-                 sh);
+                 d.leaf_cx, d.leaf_cy, d.leaf_r, d.Lall, d.xs, d.ys, d.qx, d.qy, d.perm, d.N, d.tab,
+                 d.gout, sh);
 }
 
 namespace {
 
-size_t leaf_grad_lds_bytes(int p, int use_col) {
-  return (size_t)PW * FB * 3 * sizeof(double2) +
-         (use_col ? (size_t)(p + 2) * 64 * sizeof(double) : 0);
-}
-
-size_t leaf_lds_bytes(int nw, int p, int use_col) {
-  return (size_t)nw * FB * (2 * sizeof(double2) + sizeof(float2) + sizeof(double)) +
-         (use_col ? (size_t)(p + 1) * 64 * sizeof(double) : 0);
-}
 
 template <class V>
 void upload_items(DevBuf<V>& d, const std::vector<V>& h, hipStream_t s) {
@@ -1637,6 +2065,15 @@ void FmmForest::build(const std::vector<Tree>& trees, bool p2p32, hipStream_t s)
     d.nbi = f.nbi.p;
     d.leaf_cx = f.leaf_cx.p;
     d.leaf_cy = f.leaf_cy.p;
+    d.leaf_r = f.leaf_r.p;
+    d.leaf_of = f.leaf_of.p;
+    d.p2p_pairs = f.p2p_pairs;
+    // the tree's near-field cache when it holds this forest's precision
+    const bool cached = p2p32 ? f.nc_kind == 1 : f.nc_kind == 2;
+    d.blk_off = f.blk_off.p;
+    d.nc = cached ? (p2p32 ? (const void*)f.nc32.p : (const void*)f.nc64.p) : nullptr;
+    d.nc_kind = cached ? f.nc_kind : 0;
+    d.ss = cached ? f.ss.p : nullptr;
     d.Mall = f.Mall.p;
     d.Lall = f.Lall.p;
     d.lv = f.m2l_levels();
@@ -1706,17 +2143,16 @@ void FmmForest::apply(const int* mask, const double* V, const int* col, int64_t 
 
 void FmmForest::leaves(const int* mask, hipStream_t s, unsigned long long* pairs) const {
   if (nmem == 0) return;
-  const int use_col = p <= kColMaxOrder;
+  if (n_gather) forest_l2p_kernel<<<n_gather, 256, 0, s>>>(dev.p, it_gather.p, mask, p);
   if (n_leaf2) {
     auto k = f32 ? forest_leaf_kernel<true, 2> : forest_leaf_kernel<false, 2>;
-    k<<<n_leaf2, FB * 2, leaf_lds_bytes(2, p, use_col), s>>>(dev.p, it_leaf2.p, mask, p, use_col,
-                                                             pairs);
+    k<<<n_leaf2, FB * 2, leaf_lds_bytes(2), s>>>(dev.p, it_leaf2.p, mask);
   }
   if (n_leaf4) {
     auto k = f32 ? forest_leaf_kernel<true, PW> : forest_leaf_kernel<false, PW>;
-    k<<<n_leaf4, FB * PW, leaf_lds_bytes(PW, p, use_col), s>>>(dev.p, it_leaf4.p, mask, p,
-                                                               use_col, pairs);
+    k<<<n_leaf4, FB * PW, leaf_lds_bytes(PW), s>>>(dev.p, it_leaf4.p, mask);
   }
+  if (pairs) forest_count_pairs_kernel<<<1, 256, 0, s>>>(dev.p, nmem, mask, pairs);
   YQ_HIP(hipGetLastError());
 }
 

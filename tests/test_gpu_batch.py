@@ -211,9 +211,12 @@ def test_batch_fmm_lane_matches_oracle_single_and_direct_batch(oracles):
         assert ia[c]["residual"] <= 1e-10 and _rel(_np(sa)[s], oracles[c]["sigma"]) < 1e-8
 
 
-def _lane_batch(cfgs, graphs, in_engine=True, **prm):
+def _lane_batch(cfgs, graphs, in_engine=True, near=0, **prm):
     b = yq.Batch(yq.default_params(**prm))
-    # the 5-particle configuration takes the FMM (a forest tree, or a lane problem)
+    # the 5-particle configuration takes the FMM (a forest tree, or a lane problem);
+    # near: the trees' near-field cache budget (0: the leaf passes evaluate every pair,
+    # as a standalone FMM problem does)
+    b.set_near_cache(near)
     b.set_fmm(5 * P * 16, workers=2, in_engine=in_engine)
     b.set_configs(cfgs)
     b.use_graphs(graphs)
@@ -345,7 +348,7 @@ def test_batch_raw_abi_without_device_sync_between_calls():
     torch = _torch()
     cfgs = _configs()
     prm = dict(panels_per_particle=P, qbx_order=ORDER, tol=1e-10, precision=1)
-    ref = _lane_batch(cfgs, True, **prm)
+    ref = _lane_batch(cfgs, True, near=-1, **prm)   # the library's default cache budget
     ref.set_boundary_data(ref.boundary_label())
     sref, _ = ref.solve()
     sref = _np(sref)
@@ -502,3 +505,45 @@ def test_batch_leaf_pass_timers_count_pairs_and_leave_results_unchanged():
     assert [i["iterations"] for i in infos] == [i["iterations"] for i in i_ref]
     n, ms, pairs = b.profile_read(yq.YQ_MIXED, kernel="leaf")
     assert n >= max(i["matvecs_fp32"] for i in infos) and 0 < pairs <= n * p1
+
+
+def test_batch_near_cache_matches_uncached_leaf_passes():
+    """Forest trees with their near-field coefficients cached (FP32 inner, FP64
+    residual operator) against the passes that evaluate every pair; the budget
+    decides which trees hold a cache; a cached tree alone gives the bits it gives in
+    the mix, and graph replays equal eager iterations."""
+    torch = _torch()
+    cfgs = _forest_configs()
+    prm = dict(panels_per_particle=P, qbx_order=ORDER, tol=1e-10, precision=1)
+    plain = _lane_batch(cfgs, True, near=0, **prm)
+    cached = _lane_batch(cfgs, True, near=-1, **prm)
+    held, t32, t64 = cached.near_cache_info()
+    assert (t32, t64) == (2, 2) and held > 0 and plain.near_cache_info() == (0, 0, 0)
+    x = np.random.default_rng(9).standard_normal(cached.total)
+    for prec, tol in ((yq.YQ_MIXED, 5e-6), (yq.YQ_FP64, 1e-12)):
+        a = _np(cached.apply_operator(x, prec))
+        b = _np(plain.apply_operator(x, prec))
+        for c in range(len(cfgs)):
+            s = slice(int(cached.offsets[c]), int(cached.offsets[c + 1]))
+            assert _rel(a[s], b[s]) < tol, (prec, c)
+    for bt in (plain, cached):
+        bt.set_boundary_data(bt.boundary_label())
+    sp, ip = plain.solve()
+    sc, ic = cached.solve()
+    assert all(i["residual"] <= 1e-10 for i in ic)
+    assert _rel(_np(sc), _np(sp)) < 1e-8
+    # graph replays equal eager iterations with the caches in use
+    eager = _lane_batch(cfgs, False, near=-1, **prm)
+    eager.set_boundary_data(eager.boundary_label())
+    se, _ = eager.solve()
+    assert np.array_equal(_np(se), _np(sc))
+    # alone = in the mix, bitwise, for a cached tree
+    alone = _lane_batch([cfgs[4]], True, near=-1, **prm)
+    assert alone.near_cache_info()[1:] == (1, 1)
+    alone.set_boundary_data(alone.boundary_label())
+    sa, _ = alone.solve()
+    assert np.array_equal(_np(sa), _np(sc)[int(cached.offsets[4]):int(cached.offsets[5])])
+    # a budget one byte short of every cache: the last FP64 cache is left out
+    short = _lane_batch(cfgs, True, near=held - 1, **prm)
+    assert short.near_cache_info()[1:] == (2, 1)
+    torch.cuda.synchronize()
