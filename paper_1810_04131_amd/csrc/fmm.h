@@ -59,6 +59,7 @@ struct Fmm {
   // of the P2P lists (target leaf b, source leaf nbi[e]) owns the block of
   // cnt(b) x cnt(nbi[e]) coefficients at blk_off[e], target-fastest.
   DevBuf<int64_t> blk_off;
+  DevBuf<int2> ent;                   // entry e's source range: (first sorted node, count)
   DevBuf<float> nc32;                 // FP32 coefficients (the inner operator's leaf pass)
   DevBuf<double> nc64;                // FP64 coefficients (the FP64 leaf pass)
   int nc_kind = 0;                    // 0 none, 1 FP32, 2 FP64
@@ -132,6 +133,7 @@ struct FmmDev {
   int64_t N, off;          // nodes; offset of the configuration in the batch vectors
   int64_t p2p_pairs;       // source-target pairs of one leaf pass
   const int64_t* blk_off;  // near-field cache (nc_kind 1: float, 2: double; 0: none)
+  const int2* ent;
   const void* nc;
   int nc_kind;
   double* ss;
@@ -168,6 +170,8 @@ struct FmmForest {
   DevBuf<FmmDev> dev;
   // work items (member, index within the member's launch of that pass)
   DevBuf<int2> it_gather, it_p2m, it_pack, it_m2l, it_leaf2, it_leaf4, it_leaves;
+  DevBuf<int2> it_cleaf;         // leaves of the trees whose near-field cache the pass reads
+  int n_cleaf = 0, n_leaves = 0; // n_leaves: every leaf (it_leaves)
   std::vector<DevBuf<int2>> it_tree;   // per parent level l: M2M into / L2L out of level l
   int n_gather = 0, n_p2m = 0, n_pack = 0, n_m2l = 0, n_leaf2 = 0, n_leaf4 = 0;
   std::vector<int> n_tree;

@@ -878,8 +878,7 @@ static size_t leaf_grad_lds_bytes(int p, int use_col) {
 // One block per leaf: the direct interactions of the leaf's targets with the leaves of
 // its P2P list, added to partial[node] (which holds the local expansion's value from
 // l2p_kernel) in the far-field kernels' scaling (far field * 2 pi / kappa^2).
-// Leaf b; sh: the kernel's dynamic LDS (leaf_lds_bytes); boff, nc, ssd: the
-// near-field cache when nc is set (the coefficients of the pass's precision).
+// Leaf b; sh: the kernel's dynamic LDS (leaf_lds_bytes).
 template <bool F32, int NW>
 __device__ __forceinline__ void leaf_pass(int b, double kappa, const int* __restrict__ ls,
                                           const int* __restrict__ lc,
@@ -894,9 +893,7 @@ __device__ __forceinline__ void leaf_pass(int b, double kappa, const int* __rest
                                           const double* __restrict__ qy,
                                           const int* __restrict__ perm,
                                           const double* __restrict__ tab,
-                                          double* __restrict__ partial, double* sh,
-                                          const int64_t* __restrict__ boff, const void* nc,
-                                          const double* __restrict__ ssd) {
+                                          double* __restrict__ partial, double* sh) {
   // the wave index is uniform over the wave: in a scalar register, the neighbour-leaf
   // and source loops below run on scalar counters (the LDS tiles are addressed from a
   // vector register, so the unrolled pair loop reads them with immediate offsets)
@@ -921,41 +918,6 @@ __device__ __forceinline__ void leaf_pass(int b, double kappa, const int* __rest
       const int nb = __builtin_amdgcn_readfirstlane(nbi[e]);
       const int t0 = __builtin_amdgcn_readfirstlane(ls[nb]);
       const int tc = __builtin_amdgcn_readfirstlane(lc[nb]);
-      if (nc) {
-        // cached coefficients: group g takes the sources [g S, g S + S) of the block,
-        // CB at a time with every load issued before the first use (the pass is bound
-        // by the loads in flight)
-        constexpr int CB = 8;
-        const int64_t bo = boff[e];
-        const gptr<float> cb32 = as_g(static_cast<const float*>(nc) + bo);
-        const gptr<double> cb64 = as_g(static_cast<const double*>(nc) + bo);
-        const gptr<double> sb = as_g(ssd + t0);
-        const int S = (tc + lg.G - 1) / lg.G, k0 = lg.ga * S;
-        const int kend = min(k0 + S, tc);   // this group's sources end here
-        for (int u = 0; u < S; u += CB) {
-          float c32[CB];
-          double c64[CB], sv[CB];
-#pragma unroll
-          for (int v = 0; v < CB; ++v) {
-            const int kc = min(k0 + u + v, tc - 1);
-            const int a = kc * cnt + j;   // within the block (< 2^31)
-            if (F32)
-              c32[v] = cb32[a];
-            else
-              c64[v] = cb64[a];
-            sv[v] = sb[kc];
-          }
-#pragma unroll
-          for (int v = 0; v < CB; ++v) {
-            const bool ok = k0 + u + v < kend;
-            if (F32)
-              acc32 = fmaf(ok ? c32[v] : 0.0f, (float)sv[v], acc32);
-            else
-              acc64 = fma(ok ? c64[v] : 0.0, sv[v], acc64);
-          }
-        }
-        continue;
-      }
       const int cls = leaf_class(kappa, cx, cy, lr[b], ccx[nb], ccy[nb], lr[nb]);
       for (int k0 = 0; k0 < tc; k0 += FB) {
         const int nbk = min(FB, tc - k0);
@@ -1027,14 +989,98 @@ __global__ __launch_bounds__(FB * NW) void p2p_kernel(double kappa, const int* _
                                                       const int* __restrict__ perm,
                                                       const double* __restrict__ tab,
                                                       double* __restrict__ partial,
-                                                      const int* __restrict__ stop,
-                                                      const int64_t* __restrict__ boff,
-                                                      const void* nc,
-                                                      const double* __restrict__ ssd) {
+                                                      const int* __restrict__ stop) {
   if (stop && *stop) return;
   extern __shared__ double sh[];
   leaf_pass<F32, NW>(blockIdx.x, kappa, ls, lc, nbp, nbi, ccx, ccy, lr, xs, ys, qx, qy, perm, tab,
-                     partial, sh, boff, nc, ssd);
+                     partial, sh);
+}
+
+// The leaf pass from the near-field cache, one wavefront per leaf (CW leaves per
+// block, no block barrier): entry e's coefficients, source k, target i at
+// boff[e] + k cnt + i, times the density in sorted order.  Lane groups split each
+// entry's sources; every load of a batch is issued before the first is used (the
+// pass is bound by the loads in flight).  Adds the direct sums to partial[node].
+constexpr int CW = 4;
+template <bool F32>
+__device__ __forceinline__ void leaf_cached_wave(int b, const int* __restrict__ ls,
+                                                 const int* __restrict__ lc,
+                                                 const int* __restrict__ nbp,
+                                                 const int2* __restrict__ ent,
+                                                 const int64_t* __restrict__ boff,
+                                                 const void* nc, const double* __restrict__ ssd,
+                                                 const int* __restrict__ perm,
+                                                 double* __restrict__ partial, double* red) {
+  constexpr int CB = 8;
+  const int lane = threadIdx.x % FB;
+  const int s0 = ls[b], cnt = lc[b];
+  const int e0 = nbp[b], e1 = nbp[b + 1];
+  for (int r0 = 0; r0 < cnt; r0 += FB) {
+    const LaneGroups lg = lane_groups(lane, min(cnt - r0, FB));
+    const int j = r0 + lg.t;
+    double acc64 = 0.0;
+    float acc32 = 0.0f;
+    for (int e = e0; e < e1; ++e) {
+      const int2 tt = ent[e];
+      const int t0 = __builtin_amdgcn_readfirstlane(tt.x), tc = __builtin_amdgcn_readfirstlane(tt.y);
+      const int64_t bo = boff[e];
+      const gptr<float> cb32 = as_g(static_cast<const float*>(nc) + bo);
+      const gptr<double> cb64 = as_g(static_cast<const double*>(nc) + bo);
+      const gptr<double> sb = as_g(ssd + t0);
+      const int S = (tc + lg.G - 1) / lg.G, k0 = lg.ga * S;
+      const int kend = min(k0 + S, tc);   // this group's sources end here
+      for (int u = 0; u < S; u += CB) {
+        float c32[CB];
+        double c64[CB], sv[CB];
+#pragma unroll
+        for (int v = 0; v < CB; ++v) {
+          const int kc = min(k0 + u + v, tc - 1);
+          const int a = kc * cnt + j;   // within the block (< 2^31)
+          if (F32)
+            c32[v] = cb32[a];
+          else
+            c64[v] = cb64[a];
+          sv[v] = sb[kc];
+        }
+#pragma unroll
+        for (int v = 0; v < CB; ++v) {
+          const bool ok = k0 + u + v < kend;
+          if (F32)
+            acc32 = fmaf(ok ? c32[v] : 0.0f, (float)sv[v], acc32);
+          else
+            acc64 = fma(ok ? c64[v] : 0.0, sv[v], acc64);
+        }
+      }
+    }
+    wave_sync();   // the previous round's reads of red are done
+    red[lane] = F32 ? (double)acc32 : acc64;
+    wave_sync();
+    if (lg.g == 0) {
+      double direct = 0.0;
+      for (int gg = 0; gg < lg.G; ++gg) direct += red[gg * lg.rem + lg.t];
+      const int node = perm[s0 + j];
+      partial[node] = partial[node] + direct;
+    }
+  }
+}
+
+template <bool F32>
+__global__ __launch_bounds__(FB * CW) void p2p_cached_kernel(int nleaf, const int* __restrict__ ls,
+                                                             const int* __restrict__ lc,
+                                                             const int* __restrict__ nbp,
+                                                             const int2* __restrict__ ent,
+                                                             const int64_t* __restrict__ boff,
+                                                             const void* nc,
+                                                             const double* __restrict__ ssd,
+                                                             const int* __restrict__ perm,
+                                                             double* __restrict__ partial,
+                                                             const int* __restrict__ stop) {
+  __shared__ double red[CW][FB];
+  if (stop && *stop) return;
+  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / FB));
+  const int b = blockIdx.x * CW + w;
+  if (b >= nleaf) return;
+  leaf_cached_wave<F32>(b, ls, lc, nbp, ent, boff, nc, ssd, perm, partial, red[w]);
 }
 
 // The local expansion's value at sorted node k of a tree (leaf leaf_of[k]):
@@ -1529,6 +1575,10 @@ void Fmm::build(int64_t n, double kap, int order, int lmax, const double* tab, h
         acc += (int64_t)t.leaf_cnt[k] * t.leaf_cnt[t.nbi[e]];
       }
     up(blk_off, bo);
+    std::vector<int2> en(t.nbi.size());
+    for (size_t e = 0; e < t.nbi.size(); ++e)
+      en[e] = make_int2(t.leaf_start[t.nbi[e]], t.leaf_cnt[t.nbi[e]]);
+    up(ent, en);
   }
   drop_near_cache();   // coefficients of the previous geometry
   qx.fit(n);
@@ -1650,6 +1700,7 @@ void Fmm::copy_tree(const Fmm& o, int q, const double* tab, hipStream_t s) {
   dup(leaf_cy, o.leaf_cy);
   dup(leaf_r, o.leaf_r);
   dup(blk_off, o.blk_off);
+  dup(ent, o.ent);
   dup(leaf_of, o.leaf_of);
   dup(nbp, o.nbp);
   dup(nbi, o.nbi);
@@ -1799,12 +1850,17 @@ void Fmm::apply(const double* sigma, double* partial, bool p2p_fp32, const doubl
   // the near-field cache of the apply's precision, if computed
   const void* cache = p2p_fp32 ? (nc_kind == 1 ? (const void*)nc32.p : nullptr)
                                : (nc_kind == 2 ? (const void*)nc64.p : nullptr);
-  auto k = p2p_fp32 ? (nw == 2 ? p2p_kernel<true, 2> : p2p_kernel<true, PW>)
-                    : (nw == 2 ? p2p_kernel<false, 2> : p2p_kernel<false, PW>);
-  k<<<nleaf, FB * nw, leaf_lds_bytes(nw), s>>>(kappa, leaf_start.p, leaf_cnt.p, nbp.p, nbi.p,
-                                               leaf_cx.p, leaf_cy.p, leaf_r.p, xs.p, ys.p, qx.p,
-                                               qy.p, perm.p, tab, partial, stop, blk_off.p,
-                                               cache, cache ? ss.p : nullptr);
+  if (cache) {
+    auto k = p2p_fp32 ? p2p_cached_kernel<true> : p2p_cached_kernel<false>;
+    k<<<(nleaf + CW - 1) / CW, FB * CW, 0, s>>>(nleaf, leaf_start.p, leaf_cnt.p, nbp.p, ent.p,
+                                                blk_off.p, cache, ss.p, perm.p, partial, stop);
+  } else {
+    auto k = p2p_fp32 ? (nw == 2 ? p2p_kernel<true, 2> : p2p_kernel<true, PW>)
+                      : (nw == 2 ? p2p_kernel<false, 2> : p2p_kernel<false, PW>);
+    k<<<nleaf, FB * nw, leaf_lds_bytes(nw), s>>>(kappa, leaf_start.p, leaf_cnt.p, nbp.p, nbi.p,
+                                                 leaf_cx.p, leaf_cy.p, leaf_r.p, xs.p, ys.p, qx.p,
+                                                 qy.p, perm.p, tab, partial, stop);
+  }
   YQ_HIP(hipGetLastError());
 }
 
@@ -1965,8 +2021,24 @@ __global__ __launch_bounds__(FB * NW) void forest_leaf_kernel(const FmmDev* __re
   const FmmDev& d = fd[it.x];
   if (!mask[d.cfg]) return;
   leaf_pass<F32, NW>(it.y, d.kappa, d.leaf_start, d.leaf_cnt, d.nbp, d.nbi, d.leaf_cx, d.leaf_cy,
-                     d.leaf_r, d.xs, d.ys, d.qx, d.qy, d.perm, d.tab, d.out, sh, d.blk_off, d.nc,
-                     d.ss);
+                     d.leaf_r, d.xs, d.ys, d.qx, d.qy, d.perm, d.tab, d.out, sh);
+}
+
+// The cached leaf pass over the forest: items (member, leaf) of trees holding the
+// cache of the forest's precision, CW per block.
+template <bool F32>
+__global__ __launch_bounds__(FB * CW) void forest_cleaf_kernel(const FmmDev* __restrict__ fd,
+                                                               const int2* __restrict__ items,
+                                                               int n, const int* __restrict__ mask) {
+  __shared__ double red[CW][FB];
+  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / FB));
+  const int i = blockIdx.x * CW + w;
+  if (i >= n) return;
+  const int2 it = items[i];
+  const FmmDev& d = fd[it.x];
+  if (!mask[d.cfg]) return;
+  leaf_cached_wave<F32>(it.y, d.leaf_start, d.leaf_cnt, d.nbp, d.ent, d.blk_off, d.nc, d.ss, d.perm,
+                        d.out, red[w]);
 }
 
 // l2p_kernel over the forest: items (member, 256-node block of its sorted nodes).
@@ -2030,13 +2102,13 @@ void FmmForest::build(const std::vector<Tree>& trees, bool p2p32, hipStream_t s)
   nmem = (int)trees.size();
   f32 = p2p32;
   depth = 0;
-  n_gather = n_p2m = n_pack = n_m2l = n_leaf2 = n_leaf4 = 0;
+  n_gather = n_p2m = n_pack = n_m2l = n_leaf2 = n_leaf4 = n_cleaf = n_leaves = 0;
   if (nmem == 0) return;
   p = trees[0].fmm->p;
   R16 = trees[0].fmm->R16;
   m2l32 = p2p32 && trees[0].fmm->want_m2l32;
   std::vector<FmmDev> h(nmem);
-  std::vector<int2> g, pm, pk, ml, l2, l4;
+  std::vector<int2> g, pm, pk, ml, l2, l4, cl, la;
   std::vector<std::vector<int2>> tr(DMAX + 1);
   for (int m = 0; m < nmem; ++m) {
     Fmm& f = *trees[m].fmm;
@@ -2071,6 +2143,7 @@ void FmmForest::build(const std::vector<Tree>& trees, bool p2p32, hipStream_t s)
     // the tree's near-field cache when it holds this forest's precision
     const bool cached = p2p32 ? f.nc_kind == 1 : f.nc_kind == 2;
     d.blk_off = f.blk_off.p;
+    d.ent = f.ent.p;
     d.nc = cached ? (p2p32 ? (const void*)f.nc32.p : (const void*)f.nc64.p) : nullptr;
     d.nc_kind = cached ? f.nc_kind : 0;
     d.ss = cached ? f.ss.p : nullptr;
@@ -2106,11 +2179,12 @@ void FmmForest::build(const std::vector<Tree>& trees, bool p2p32, hipStream_t s)
       for (int64_t b = 0; b < (ne + 255) / 256; ++b) pk.push_back(make_int2(m, (int)b));
       for (int t = 0; t < f.n_m2l_tiles; ++t) ml.push_back(make_int2(m, t));
     }
-    auto& lst = f.nleaf >= kLeavesFor2 ? l2 : l4;
-    for (int b = 0; b < f.nleaf; ++b) lst.push_back(make_int2(m, b));
+    auto& lst = cached ? cl : f.nleaf >= kLeavesFor2 ? l2 : l4;
+    for (int b = 0; b < f.nleaf; ++b) {
+      lst.push_back(make_int2(m, b));
+      la.push_back(make_int2(m, b));   // every leaf (the gradient pass takes PW waves for all)
+    }
   }
-  std::vector<int2> la(l2);   // every leaf (the gradient pass takes PW waves for all)
-  la.insert(la.end(), l4.begin(), l4.end());
   dev.fit(nmem);
   YQ_HIP(hipMemcpyAsync(dev.p, h.data(), nmem * sizeof(FmmDev), hipMemcpyHostToDevice, s));
   upload_items(it_gather, g, s);
@@ -2120,6 +2194,9 @@ void FmmForest::build(const std::vector<Tree>& trees, bool p2p32, hipStream_t s)
   upload_items(it_leaf2, l2, s);
   upload_items(it_leaf4, l4, s);
   upload_items(it_leaves, la, s);
+  upload_items(it_cleaf, cl, s);
+  n_cleaf = (int)cl.size();
+  n_leaves = (int)la.size();
   n_gather = (int)g.size();
   n_p2m = (int)pm.size();
   n_pack = (int)pk.size();
@@ -2152,6 +2229,10 @@ void FmmForest::leaves(const int* mask, hipStream_t s, unsigned long long* pairs
     auto k = f32 ? forest_leaf_kernel<true, PW> : forest_leaf_kernel<false, PW>;
     k<<<n_leaf4, FB * PW, leaf_lds_bytes(PW), s>>>(dev.p, it_leaf4.p, mask);
   }
+  if (n_cleaf) {
+    auto k = f32 ? forest_cleaf_kernel<true> : forest_cleaf_kernel<false>;
+    k<<<(n_cleaf + CW - 1) / CW, FB * CW, 0, s>>>(dev.p, it_cleaf.p, n_cleaf, mask);
+  }
   if (pairs) forest_count_pairs_kernel<<<1, 256, 0, s>>>(dev.p, nmem, mask, pairs);
   YQ_HIP(hipGetLastError());
 }
@@ -2166,7 +2247,7 @@ void FmmForest::leaves_grad(const int* mask, hipStream_t s) const {
   YQ_REQUIRE(!f32, YQ_EINVAL, "FMM forest: the gradient is FP64");
   if (nmem == 0) return;
   const int use_col = p <= kColMaxOrder;
-  const int nl = n_leaf2 + n_leaf4;
+  const int nl = n_leaves;
   if (nl)
     forest_leaf_grad_kernel<<<nl, FB * PW, leaf_grad_lds_bytes(p, use_col), s>>>(
         dev.p, it_leaves.p, mask, p, use_col);
