@@ -180,6 +180,12 @@ template <class T>
 __device__ __forceinline__ gptr<T> as_g(const T* p) {
   return (gptr<T>)p;
 }
+template <class T>
+using gmut = __attribute__((address_space(1))) T*;
+template <class T>
+__device__ __forceinline__ gmut<T> as_gm(T* p) {
+  return (gmut<T>)p;
+}
 
 // Geometry of one problem as the kernels see it (all device pointers).
 struct GeomView {

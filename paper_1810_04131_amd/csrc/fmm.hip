@@ -141,16 +141,17 @@ __device__ __forceinline__ double l2p_value(double xi, double yi, double cx, dou
   const double2 e1 = rho > 0.0 ? make_double2(dx / rho, dy / rho) : make_double2(1.0, 0.0);
   const double2 z = make_double2(hx * e1.x, hx * e1.y);
   double hi = iscaled_series(t, p + 1), cur = iscaled_series(t, p);
-  double2 R = make_double2(lb[p].x * cur, lb[p].y * cur);
+  const gptr<double> lg = as_g(reinterpret_cast<const double*>(lb));   // (re, im) pairs
+  double2 R = make_double2(lg[2 * p] * cur, lg[2 * p + 1] * cur);
   for (int n = p; n >= 1; --n) {
     const double prev = fma(t * hi, recip(n) * recip(n + 1), cur);   // It_{n-1}
     const double2 Rz = cmul(R, z);
-    const double2 L = lb[n - 1];
+    const double2 L = make_double2(lg[2 * n - 2], lg[2 * n - 1]);
     R = make_double2(fma(L.x, prev, Rz.x * recip(n)), fma(L.y, prev, Rz.y * recip(n)));
     hi = cur;
     cur = prev;
   }
-  return 2.0 * R.x - lb[0].x * cur;
+  return 2.0 * R.x - lg[0] * cur;
 }
 
 // Sum over the 64 lanes of a wave (fixed butterfly order: the same bits on every run).
@@ -240,10 +241,10 @@ __device__ __forceinline__ void gather_one(int64_t k, const int* __restrict__ pe
                                            const double* __restrict__ wnxs,
                                            const double* __restrict__ wnys, double* __restrict__ qx,
                                            double* __restrict__ qy, double* __restrict__ ss) {
-  const double s = sigma[perm[k]];
-  qx[k] = wnxs[k] * s;
-  qy[k] = wnys[k] * s;
-  if (ss) ss[k] = s;
+  const double s = as_g(sigma)[as_g(perm)[k]];
+  as_gm(qx)[k] = as_g(wnxs)[k] * s;
+  as_gm(qy)[k] = as_g(wnys)[k] * s;
+  if (ss) as_gm(ss)[k] = s;
 }
 
 __global__ void gather_kernel(int64_t N, const int* __restrict__ perm, const double* __restrict__ sigma,
@@ -273,8 +274,8 @@ __device__ __forceinline__ void p2m_leaf(int b, int p, int use_col, double kappa
                                          const double* __restrict__ qy, double2* __restrict__ M,
                                          double* itab) {
   const int lane = threadIdx.x;
-  const int s0 = ls[b], cnt = lc[b];
-  const double cx = ccx[b], cy = ccy[b];
+  const int s0 = as_k(ls)[b], cnt = as_k(lc)[b];
+  const double cx = as_k(ccx)[b], cy = as_k(ccy)[b];
   double* col = itab + lane;
   double2 mine = make_double2(0.0, 0.0);
   for (int r0 = 0; r0 < cnt; r0 += 64) {
@@ -282,9 +283,9 @@ __device__ __forceinline__ void p2m_leaf(int b, int p, int use_col, double kappa
     double dx = 0.0, dy = 0.0;
     double2 Q = make_double2(0.0, 0.0);
     if (j < cnt) {
-      dx = xs[s0 + j] - cx;
-      dy = ys[s0 + j] - cy;
-      Q = make_double2(qx[s0 + j], qy[s0 + j]);
+      dx = as_g(xs)[s0 + j] - cx;
+      dy = as_g(ys)[s0 + j] - cy;
+      Q = make_double2(as_g(qx)[s0 + j], as_g(qy)[s0 + j]);
     }
     const double rho = sqrt(dx * dx + dy * dy);
     const double x = kappa * rho, t = 0.25 * x * x, hx = 0.5 * x;
@@ -904,21 +905,23 @@ __device__ __forceinline__ void leaf_pass(int b, double kappa, const int* __rest
   double2* sq = sbase + (NW + wv) * 2 * FB;                            // [NW][2 FB] (FP64)
   float2* sq32 = reinterpret_cast<float2*>(sq);                        // (FP32, same space)
   double* red = reinterpret_cast<double*>(sbase + 4 * NW * FB);        // [NW][FB] wave sums
-  const int s0 = ls[b], cnt = lc[b];
+  // leaf and list data through scalar loads (uniform over the wave)
+  const int s0 = as_k(ls)[b], cnt = as_k(lc)[b];
   const double kap2 = kappa * kappa;
-  const double cx = ccx[b], cy = ccy[b];
+  const double cx = as_k(ccx)[b], cy = as_k(ccy)[b], rb = as_k(lr)[b];
+  const int e0 = as_k(nbp)[b], e1 = as_k(nbp)[b + 1];
   for (int r0 = 0; r0 < cnt; r0 += FB) {
     const LaneGroups lg = lane_groups(lane, min(cnt - r0, FB));
     const int j = r0 + lg.t;
-    const double xi = xs[s0 + j], yi = ys[s0 + j];
+    const double xi = as_g(xs)[s0 + j], yi = as_g(ys)[s0 + j];
     const bool act = lg.g == 0;   // one lane per target: the sums of every wave and group
     double acc64 = 0.0;
     float acc32 = 0.0f;
-    for (int e = nbp[b] + w; e < nbp[b + 1]; e += NW) {
-      const int nb = __builtin_amdgcn_readfirstlane(nbi[e]);
-      const int t0 = __builtin_amdgcn_readfirstlane(ls[nb]);
-      const int tc = __builtin_amdgcn_readfirstlane(lc[nb]);
-      const int cls = leaf_class(kappa, cx, cy, lr[b], ccx[nb], ccy[nb], lr[nb]);
+    for (int e = e0 + w; e < e1; e += NW) {
+      const int nb = as_k(nbi)[e];
+      const int t0 = as_k(ls)[nb];
+      const int tc = as_k(lc)[nb];
+      const int cls = leaf_class(kappa, cx, cy, rb, as_k(ccx)[nb], as_k(ccy)[nb], as_k(lr)[nb]);
       for (int k0 = 0; k0 < tc; k0 += FB) {
         const int nbk = min(FB, tc - k0);
         const int S = (nbk + lg.G - 1) / lg.G;
@@ -967,8 +970,8 @@ __device__ __forceinline__ void leaf_pass(int b, double kappa, const int* __rest
       for (int q = 0; q < NW; ++q)
         for (int gg = 0; gg < lg.G; ++gg) direct += red[q * FB + gg * lg.rem + lg.t];
       // the local expansion's value is there already (l2p_kernel)
-      const int node = perm[s0 + j];
-      partial[node] = partial[node] + direct;
+      const int node = as_g(perm)[s0 + j];
+      as_gm(partial)[node] = as_g(partial)[node] + direct;
     }
     __syncthreads();   // red is rewritten by the next group of targets
   }
@@ -1013,17 +1016,18 @@ __device__ __forceinline__ void leaf_cached_wave(int b, const int* __restrict__ 
                                                  double* __restrict__ partial, double* red) {
   constexpr int CB = 8;
   const int lane = threadIdx.x % FB;
-  const int s0 = ls[b], cnt = lc[b];
-  const int e0 = nbp[b], e1 = nbp[b + 1];
+  // leaf and list data through scalar loads (uniform over the wave)
+  const int s0 = as_k(ls)[b], cnt = as_k(lc)[b];
+  const int e0 = as_k(nbp)[b], e1 = as_k(nbp)[b + 1];
   for (int r0 = 0; r0 < cnt; r0 += FB) {
     const LaneGroups lg = lane_groups(lane, min(cnt - r0, FB));
     const int j = r0 + lg.t;
     double acc64 = 0.0;
     float acc32 = 0.0f;
     for (int e = e0; e < e1; ++e) {
-      const int2 tt = ent[e];
-      const int t0 = __builtin_amdgcn_readfirstlane(tt.x), tc = __builtin_amdgcn_readfirstlane(tt.y);
-      const int64_t bo = boff[e];
+      const kptr<int> te = as_k(reinterpret_cast<const int*>(ent)) + 2 * e;
+      const int t0 = te[0], tc = te[1];
+      const int64_t bo = as_k(boff)[e];
       const gptr<float> cb32 = as_g(static_cast<const float*>(nc) + bo);
       const gptr<double> cb64 = as_g(static_cast<const double*>(nc) + bo);
       const gptr<double> sb = as_g(ssd + t0);
@@ -1058,8 +1062,8 @@ __device__ __forceinline__ void leaf_cached_wave(int b, const int* __restrict__ 
     if (lg.g == 0) {
       double direct = 0.0;
       for (int gg = 0; gg < lg.G; ++gg) direct += red[gg * lg.rem + lg.t];
-      const int node = perm[s0 + j];
-      partial[node] = partial[node] + direct;
+      const int node = as_g(perm)[s0 + j];
+      as_gm(partial)[node] = as_g(partial)[node] + direct;
     }
   }
 }
@@ -1095,10 +1099,10 @@ __device__ __forceinline__ void l2p_node(int64_t k, int p, double kappa,
                                          const int* __restrict__ perm,
                                          const double2* __restrict__ L,
                                          double* __restrict__ partial) {
-  const int b = leaf_of[k];
-  const double u = l2p_value(xs[k], ys[k], ccx[b], ccy[b], kappa, p,
-                             L + (int64_t)gid[b] * (p + 1));
-  partial[perm[k]] = u * (2.0 * PI / (kappa * kappa));
+  const int b = as_g(leaf_of)[k];
+  const double u = l2p_value(as_g(xs)[k], as_g(ys)[k], as_g(ccx)[b], as_g(ccy)[b], kappa, p,
+                             L + (int64_t)as_g(gid)[b] * (p + 1));
+  as_gm(partial)[as_g(perm)[k]] = u * (2.0 * PI / (kappa * kappa));
 }
 
 __global__ __launch_bounds__(256) void l2p_kernel(int64_t N, int p, double kappa,
@@ -1153,19 +1157,20 @@ __device__ __forceinline__ void leaf_grad_pass(int b, int p, int use_col, double
   double2* sq = sbase + (PW + wv) * 2 * FB;                    // [PW][2 FB]
   double2* red = sbase + 4 * PW * FB;                          // [PW][FB] wave sums (x, y)
   double* col = reinterpret_cast<double*>(red + PW * FB) + lane;   // [(p + 2) * 64] scaled I_n
-  const int s0 = ls[b], cnt = lc[b];
+  const int s0 = as_k(ls)[b], cnt = as_k(lc)[b];
   const double kap2 = kappa * kappa;
-  const double cx = ccx[b], cy = ccy[b];
+  const double cx = as_k(ccx)[b], cy = as_k(ccy)[b], rb = as_k(lr)[b];
+  const int e0 = as_k(nbp)[b], e1 = as_k(nbp)[b + 1];
   for (int r0 = 0; r0 < cnt; r0 += FB) {
     const LaneGroups lg = lane_groups(lane, min(cnt - r0, FB));
     const int j = r0 + lg.t;
-    const double xi = xs[s0 + j], yi = ys[s0 + j];
+    const double xi = as_g(xs)[s0 + j], yi = as_g(ys)[s0 + j];
     double ax = 0.0, ay = 0.0;
-    for (int e = nbp[b] + w; e < nbp[b + 1]; e += PW) {
-      const int nb = __builtin_amdgcn_readfirstlane(nbi[e]);
-      const int t0 = __builtin_amdgcn_readfirstlane(ls[nb]);
-      const int tc = __builtin_amdgcn_readfirstlane(lc[nb]);
-      const int cls = leaf_class(kappa, cx, cy, lr[b], ccx[nb], ccy[nb], lr[nb]);
+    for (int e = e0 + w; e < e1; e += PW) {
+      const int nb = as_k(nbi)[e];
+      const int t0 = as_k(ls)[nb];
+      const int tc = as_k(lc)[nb];
+      const int cls = leaf_class(kappa, cx, cy, rb, as_k(ccx)[nb], as_k(ccy)[nb], as_k(lr)[nb]);
       for (int k0 = 0; k0 < tc; k0 += FB) {
         const int nbk = min(FB, tc - k0);
         const int S = (nbk + lg.G - 1) / lg.G;
@@ -1208,7 +1213,7 @@ __device__ __forceinline__ void leaf_grad_pass(int b, int p, int use_col, double
       const double rho = sqrt(dx * dx + dy * dy);
       const double x = kappa * rho, t = 0.25 * x * x, hx = 0.5 * x;
       const double2 e1 = rho > 0.0 ? make_double2(dx / rho, dy / rho) : make_double2(1.0, 0.0);
-      const double2* lb = L + (int64_t)gid[b] * (p + 1);
+      const double2* lb = L + (int64_t)as_k(gid)[b] * (p + 1);
       if (use_col) iscaled_col(t, p + 1, col);
       double pref = hx;                                   // (x/2)^{n+1} / (n+1)!
       double Iprev = use_col ? col[0] : iorder(t, 1.0, 0);        // I_{n-1}
@@ -2020,8 +2025,10 @@ __global__ __launch_bounds__(FB * NW) void forest_leaf_kernel(const FmmDev* __re
   const int2 it = items[blockIdx.x];
   const FmmDev& d = fd[it.x];
   if (!mask[d.cfg]) return;
+  // (the Bessel table through scalar loads, as from a kernel argument)
   leaf_pass<F32, NW>(it.y, d.kappa, d.leaf_start, d.leaf_cnt, d.nbp, d.nbi, d.leaf_cx, d.leaf_cy,
-                     d.leaf_r, d.xs, d.ys, d.qx, d.qy, d.perm, d.tab, d.out, sh);
+                     d.leaf_r, d.xs, d.ys, d.qx, d.qy, d.perm, (const double*)as_k(d.tab), d.out,
+                     sh);
 }
 
 // The cached leaf pass over the forest: items (member, leaf) of trees holding the
@@ -2082,8 +2089,8 @@ __global__ __launch_bounds__(FB * PW) void forest_leaf_grad_kernel(const FmmDev*
   const FmmDev& d = fd[it.x];
   if (!mask[d.cfg]) return;
   leaf_grad_pass(it.y, p, use_col, d.kappa, d.leaf_start, d.leaf_cnt, d.leaf_gid, d.nbp, d.nbi,
-                 d.leaf_cx, d.leaf_cy, d.leaf_r, d.Lall, d.xs, d.ys, d.qx, d.qy, d.perm, d.N, d.tab,
-                 d.gout, sh);
+                 d.leaf_cx, d.leaf_cy, d.leaf_r, d.Lall, d.xs, d.ys, d.qx, d.qy, d.perm, d.N,
+                 (const double*)as_k(d.tab), d.gout, sh);
 }
 
 namespace {
