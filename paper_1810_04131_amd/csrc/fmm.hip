@@ -453,15 +453,15 @@ struct TileOps {
 template <int KS>
 __device__ __forceinline__ void tile_load(TileOps<KS>& op, const double* __restrict__ A,
                                           const double2* __restrict__ ms, int P1, int kk) {
+  // (global loads: the pointers may come from the trees' descriptors)
+  const gptr<double> Ag = as_g(A);
+  const gptr<double> mg = as_g(reinterpret_cast<const double*>(ms));
 #pragma unroll
   for (int ks = 0; ks < KS; ++ks) {
-    op.a[ks] = A[ks * 64];
+    op.a[ks] = Ag[ks * 64];
     const int k = 4 * ks + kk;
     double b = 0.0;
-    if (ms != nullptr && k < 2 * P1) {
-      const double2 mv = ms[k < P1 ? k : k - P1];
-      b = k < P1 ? mv.x : mv.y;
-    }
+    if (ms != nullptr && k < 2 * P1) b = k < P1 ? mg[2 * k] : mg[2 * (k - P1) + 1];
     op.b[ks] = b;
   }
 }
@@ -477,13 +477,12 @@ __device__ __forceinline__ dbl4 tile_mfma(const TileOps<KS>& op, dbl4 acc) {
 // FP64 16x16 result layout: lane l holds column l % 16, its register j row 4 j + l / 16.
 template <bool ADD>
 __device__ __forceinline__ void tile_store(double2* __restrict__ y, int rt, int kk, int P1, dbl4 acc) {
+  const gmut<double> yg = as_gm(reinterpret_cast<double*>(y));   // (re, im) pairs
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     const int r = rt * 16 + 4 * j + kk;
-    if (r < P1)
-      y[r].x = ADD ? y[r].x + acc[j] : acc[j];
-    else if (r < 2 * P1)
-      y[r - P1].y = ADD ? y[r - P1].y + acc[j] : acc[j];
+    const int a = r < P1 ? 2 * r : 2 * (r - P1) + 1;
+    if (r < 2 * P1) yg[a] = ADD ? yg[a] + acc[j] : acc[j];
   }
 }
 
@@ -546,15 +545,14 @@ __device__ __forceinline__ void m2l_pack_one(int64_t t, int p, int R, int64_t g0
   double v = 0.0;
   if (k < 2 * P1) {
     const int n = k < P1 ? k : k - P1;
-    const double2 m = Mall[g * P1 + n];
-    v = k < P1 ? m.x : m.y;
+    v = as_g(reinterpret_cast<const double*>(Mall))[2 * (g * P1 + n) + (k < P1 ? 0 : 1)];
     if (sizeof(T) == 4) {
       int l = 2;
       while (g >= lv.off[l + 1]) ++l;
-      v *= msc[(int64_t)l * P1 + n];
+      v *= as_g(msc)[(int64_t)l * P1 + n];
     }
   }
-  Mp[g * R + e] = (T)v;
+  as_gm(Mp)[g * R + e] = (T)v;
 }
 
 template <typename T>
@@ -586,12 +584,12 @@ __device__ __forceinline__ void m2l_tile(int2 tl, int p, const M2LLevels& lv,
   using acc_t = typename std::conditional<F32, f32x4, dbl4>::type;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int l = tl.x, nbox = lv.nbox[l];
-  const int* __restrict__ ild = lv.ild[l];
+  const gptr<int> ild = as_g(lv.ild[l]);
   const int P1 = p + 1;
   const int col = lane & 15, kk = lane >> 4;
   const int tb = tl.y + col;
-  const T* Ml = Mp + lv.off[l] * R + kk * KS;
-  const T* Al = amat + (int64_t)l * 49 * RT * 64 * KS + (int64_t)lane * KS;
+  const gptr<T> Ml = as_g(Mp + lv.off[l] * R + kk * KS);
+  const gptr<T> Al = as_g(amat + (int64_t)l * 49 * RT * 64 * KS + (int64_t)lane * KS);
   acc_t acc[RT];
 #pragma unroll
   for (int rt = 0; rt < RT; ++rt) acc[rt] = acc_t{0, 0, 0, 0};
@@ -600,12 +598,12 @@ __device__ __forceinline__ void m2l_tile(int2 tl, int p, const M2LLevels& lv,
     const int src = tb < nbox ? ild[(int64_t)tb * 49 + o] : -1;
     if (__ballot(src >= 0) == 0) continue;    // no source at this offset in the tile
     T b[KS];
-    const T* mb = Ml + (int64_t)(src >= 0 ? src : 0) * R;
+    const gptr<T> mb = Ml + (int64_t)(src >= 0 ? src : 0) * R;
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) b[ks] = src >= 0 ? mb[ks] : T(0);
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt) {
-      const T* A = Al + ((int64_t)o * RT + rt) * 64 * KS;
+      const gptr<T> A = Al + ((int64_t)o * RT + rt) * 64 * KS;
 #pragma unroll
       for (int ks = 0; ks < KS; ++ks) {
         if constexpr (F32)
@@ -622,8 +620,8 @@ __device__ __forceinline__ void m2l_tile(int2 tl, int p, const M2LLevels& lv,
           dbl4{(double)acc[rt][0], (double)acc[rt][1], (double)acc[rt][2], (double)acc[rt][3]};
   __syncthreads();
   if (wave != 0 || tb >= nbox) return;
-  double2* y = lv.L[l] + (int64_t)tb * P1;
-  const double* sc = F32 ? msc + (int64_t)l * P1 : nullptr;
+  const gmut<double> y = as_gm(reinterpret_cast<double*>(lv.L[l] + (int64_t)tb * P1));
+  const gptr<double> sc = as_g(F32 ? msc + (int64_t)l * P1 : msc);
 #pragma unroll
   for (int rt = 0; rt < RT; ++rt) {
     dbl4 v = {(double)acc[rt][0], (double)acc[rt][1], (double)acc[rt][2], (double)acc[rt][3]};
@@ -632,9 +630,9 @@ __device__ __forceinline__ void m2l_tile(int2 tl, int p, const M2LLevels& lv,
     for (int j = 0; j < 4; ++j) {
       const int r = F32 ? rt * 16 + 4 * kk + j : rt * 16 + 4 * j + kk;
       if (r < P1)
-        y[r].x = F32 ? v[j] * sc[r] : v[j];
+        y[2 * r] = F32 ? v[j] * sc[r] : v[j];
       else if (r < 2 * P1)
-        y[r - P1].y = F32 ? v[j] * sc[r - P1] : v[j];
+        y[2 * (r - P1) + 1] = F32 ? v[j] * sc[r - P1] : v[j];
     }
   }
 }
@@ -668,15 +666,16 @@ __device__ __forceinline__ void tree_tile(int bx, int p, int nbox, const int* __
   const int col = lane & 15, kk = lane >> 4;
   const int tb = (bx / RT) * 16 + col;
   const double* A = amat + (int64_t)pos * R * R + (int64_t)rt * KS * 64 + lane;
-  const int c = tb < nbox ? ch[4 * (int64_t)tb + pos] : -1;
+  const gptr<int> chg = as_g(ch);
+  const int c = tb < nbox ? chg[4 * (int64_t)tb + pos] : -1;
   TileOps<KS> op;
   if (GATHER) {
     tile_load<KS>(op, A, c >= 0 ? X + (int64_t)c * P1 : nullptr, P1, kk);
     dbl4 acc = tile_mfma<KS>(op, dbl4{0.0, 0.0, 0.0, 0.0});
     acc = block_tile_sum(acc, red);
     // a leaf keeps the coefficients of its own nodes (P2M)
-    const bool split = tb < nbox && (ch[4 * (int64_t)tb] >= 0 || ch[4 * (int64_t)tb + 1] >= 0 ||
-                                     ch[4 * (int64_t)tb + 2] >= 0 || ch[4 * (int64_t)tb + 3] >= 0);
+    const bool split = tb < nbox && (chg[4 * (int64_t)tb] >= 0 || chg[4 * (int64_t)tb + 1] >= 0 ||
+                                     chg[4 * (int64_t)tb + 2] >= 0 || chg[4 * (int64_t)tb + 3] >= 0);
     if (pos == 0 && split) tile_store<false>(Y + (int64_t)tb * P1, rt, kk, P1, acc);
   } else {
     if (__ballot(c >= 0) == 0) return;          // whole wave: no child at this position
