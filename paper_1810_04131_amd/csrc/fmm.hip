@@ -1013,28 +1013,34 @@ __device__ __forceinline__ void leaf_cached_wave(int b, const int* __restrict__ 
                                                  const void* nc, const double* __restrict__ ssd,
                                                  const int* __restrict__ perm,
                                                  double* __restrict__ partial, double* red) {
-  constexpr int CB = 8;
+  constexpr int CB = 16;
   const int lane = threadIdx.x % FB;
   // leaf and list data through scalar loads (uniform over the wave)
   const int s0 = as_k(ls)[b], cnt = as_k(lc)[b];
   const int e0 = as_k(nbp)[b], e1 = as_k(nbp)[b + 1];
+  const kptr<int> te = as_k(reinterpret_cast<const int*>(ent));
   for (int r0 = 0; r0 < cnt; r0 += FB) {
     const LaneGroups lg = lane_groups(lane, min(cnt - r0, FB));
     const int j = r0 + lg.t;
+    // the target's output and its current value (the local expansion's), early
+    const int node = lg.g == 0 ? as_g(perm)[s0 + j] : 0;
+    const double prev = lg.g == 0 ? as_g(partial)[node] : 0.0;
     double acc64 = 0.0;
     float acc32 = 0.0f;
     for (int e = e0; e < e1; ++e) {
-      const kptr<int> te = as_k(reinterpret_cast<const int*>(ent)) + 2 * e;
-      const int t0 = te[0], tc = te[1];
+      const int t0 = te[2 * e], tc = te[2 * e + 1];
       const int64_t bo = as_k(boff)[e];
       const gptr<float> cb32 = as_g(static_cast<const float*>(nc) + bo);
       const gptr<double> cb64 = as_g(static_cast<const double*>(nc) + bo);
-      const gptr<double> sb = as_g(ssd + t0);
+      // the source leaf's densities, one per lane, handed to the lanes that need them
+      // through the cross-lane permute (tc <= 64: a leaf holds at most 64 nodes)
+      const double sl = lane < tc ? as_g(ssd)[t0 + lane] : 0.0;
+      const float sl32 = (float)sl;
       const int S = (tc + lg.G - 1) / lg.G, k0 = lg.ga * S;
       const int kend = min(k0 + S, tc);   // this group's sources end here
       for (int u = 0; u < S; u += CB) {
         float c32[CB];
-        double c64[CB], sv[CB];
+        double c64[CB];
 #pragma unroll
         for (int v = 0; v < CB; ++v) {
           const int kc = min(k0 + u + v, tc - 1);
@@ -1043,15 +1049,19 @@ __device__ __forceinline__ void leaf_cached_wave(int b, const int* __restrict__ 
             c32[v] = cb32[a];
           else
             c64[v] = cb64[a];
-          sv[v] = sb[kc];
         }
 #pragma unroll
         for (int v = 0; v < CB; ++v) {
-          const bool ok = k0 + u + v < kend;
-          if (F32)
-            acc32 = fmaf(ok ? c32[v] : 0.0f, (float)sv[v], acc32);
-          else
-            acc64 = fma(ok ? c64[v] : 0.0, sv[v], acc64);
+          const int k = k0 + u + v;
+          const bool ok = k < kend;
+          const int kc = min(k, tc - 1);
+          if (F32) {
+            const float sv = __shfl(sl32, kc, FB);
+            acc32 = fmaf(ok ? c32[v] : 0.0f, sv, acc32);
+          } else {
+            const double sv = __shfl(sl, kc, FB);
+            acc64 = fma(ok ? c64[v] : 0.0, sv, acc64);
+          }
         }
       }
     }
@@ -1061,8 +1071,7 @@ __device__ __forceinline__ void leaf_cached_wave(int b, const int* __restrict__ 
     if (lg.g == 0) {
       double direct = 0.0;
       for (int gg = 0; gg < lg.G; ++gg) direct += red[gg * lg.rem + lg.t];
-      const int node = as_g(perm)[s0 + j];
-      as_gm(partial)[node] = as_g(partial)[node] + direct;
+      as_gm(partial)[node] = prev + direct;
     }
   }
 }
