@@ -153,7 +153,7 @@ def parse():
                          "(bfar32_kernel)")
     ap.add_argument("--near-cache-gb", type=float, default=None,
                     help="batch: device memory for the FMM trees' near-field caches (GB; 0 "
-                         "none; default: the library's, half of the free memory)")
+                         "none; default: the library's, the free memory less a reserve)")
     ap.add_argument("--fmm-min-nodes", type=int, default=None,
                     help="batch: configurations of at least this many nodes take the FMM "
                          "(default 0 for hybrid: every configuration is a tree of the forest, "

@@ -368,7 +368,9 @@ int yq_batch_set_fmm_engine(yq_batch* batch, int32_t enable);
  * them instead of evaluating K1 (a block-sparse matrix-vector product).
  * max_bytes: the most device memory the caches may hold (FP32 caches of every tree
  * first, then FP64 ones, in configuration order, while they fit); 0 disables; -1
- * (default): half of the device memory free when the configurations are set.
+ * (default): the device memory free when the configurations are set, less a
+ * reserve of a tenth of the device memory (at least 8 GiB).  The FP32 caches also
+ * hold the P2M coefficients of the inner operator's multipoles.
  * Results agree with the uncached passes to rounding.  Before yq_batch_set_configs
  * (YQ_ESTATE after).  yq_batch_near_cache_info: bytes held and the number of
  * trees with an FP32 / FP64 cache (outputs may be NULL). */

@@ -285,7 +285,7 @@ class Batch:
 
     def set_near_cache(self, max_bytes=-1):
         """Device memory for the FMM trees' near-field caches (before set_configs):
-        -1 half of the free memory (default), 0 none."""
+        -1 the free memory less a reserve (default), 0 none."""
         self._check(self.lib.yq_batch_set_near_cache(self.h, int(max_bytes)))
         return self
 

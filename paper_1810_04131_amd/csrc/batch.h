@@ -26,6 +26,7 @@ struct ConfDev {
   Far32View f32;          // FP32 far-field view (its src is the configuration's own records)
   const float2* rel;      // scaled relative positions (pack input)
   const double* W;
+  const float* W32;       // W in FP32 for the inner operator (null: W)
   const int* xrow;
   const int* xpan;
   const double* xvals;
@@ -93,8 +94,9 @@ struct Engine {
   // leaf pairs and M2L) and the FP64 residual operator (the members' order-40 FMMs)
   FmmForest forest_in, forest_hi;
   // near-field caches of the forest trees (FP32 coefficients for the inner operator
-  // first, then FP64 for the residual operator): at most this many bytes; -1: half of
-  // the device memory free at the rebuild (with the caches already held)
+  // first, then FP64 for the residual operator): at most this many bytes; -1: the
+  // device memory free at the rebuild (with the caches already held) less a reserve of
+  // a tenth of the device memory (at least 8 GiB)
   int64_t near_budget = -1;
   int64_t near_bytes = 0;      // bytes the caches hold
   int near_trees32 = 0, near_trees64 = 0;

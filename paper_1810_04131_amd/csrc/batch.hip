@@ -341,7 +341,10 @@ __global__ void bfinish_kernel(const ConfDev* __restrict__ cf, const int* __rest
     for (int k = 0; k < cd.chunks32; ++k) s += (double)cd.part32[(int64_t)k * N + i];
   }
   s *= cd.kappa * cd.kappa / (2.0 * PI);
-  const double corr = correction_row(i, N, cd.P, cd.win, cd.W, cd.xrow, cd.xpan, cd.xvals, sg);
+  // the inner (FP32) operator reads the correction in FP32 when it is there
+  const double corr =
+      f32 && cd.W32 ? correction_row(i, N, cd.P, cd.win, cd.W32, cd.xrow, cd.xpan, cd.xvals, sg)
+                    : correction_row(i, N, cd.P, cd.win, cd.W, cd.xrow, cd.xpan, cd.xvals, sg);
   out[g] = s + corr;
 }
 
@@ -726,6 +729,11 @@ __global__ void baxpby_kernel(const int* __restrict__ node_conf, int64_t T,
   out[g] = a * x[g] + (y ? b * y[g] : 0.0);
 }
 
+__global__ void round_f32_kernel(const double* __restrict__ a, int64_t n, float* __restrict__ b) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) b[i] = (float)a[i];
+}
+
 __global__ void fill_int_kernel(int* __restrict__ p, int64_t n, int v) {
   const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (g < n) p[g] = v;
@@ -784,6 +792,16 @@ void Engine::rebuild() {
       d.f32 = pb->far32();
       d.rel = pb->frel.p;
       d.W = pb->W.p;
+      if (prm.precision == YQ_MIXED && pb->W.n) {
+        if (pb->W32.n != pb->W.n || pb->W32_src != pb->W.p) {
+          pb->W32.alloc(pb->W.n);
+          round_f32_kernel<<<nb256((int64_t)pb->W.n), 256, 0, stream>>>(pb->W.p, (int64_t)pb->W.n,
+                                                                        pb->W32.p);
+          YQ_HIP(hipGetLastError());
+          pb->W32_src = pb->W.p;
+        }
+        d.W32 = pb->W32.p;
+      }
       d.xrow = pb->xrow.p;
       d.xpan = pb->xpan.p;
       d.xvals = pb->x_total > 0 ? pb->xvals.p : nullptr;
@@ -860,19 +878,26 @@ void Engine::rebuild() {
   if (nfitems)
     YQ_HIP(hipMemcpyAsync(fitems.p, fi.data(), nfitems * sizeof(int2), hipMemcpyHostToDevice, stream));
   pen.alloc(std::max<int64_t>(npart, 1));
+  // the Krylov basis and work vectors before the caches, which take what is left
+  V.reserve((size_t)(m + 1) * std::max<int64_t>(T, 1));
+  w.reserve(std::max<int64_t>(T, 1));
+  r.reserve(std::max<int64_t>(T, 1));
+  tmp.reserve(std::max<int64_t>(T, 1));
+  delta.reserve(std::max<int64_t>(T, 1));
+  f.reserve(std::max<int64_t>(T, 1));
   // near-field caches within the budget, FP32 (inner operator, every iteration)
   // first; a tree keeps its cache until its geometry changes
   {
     int64_t held = 0;
     for (auto* tv : {&tin, &thi})
       for (auto& t : *tv)
-        if (t.fmm->nc_kind)
-          held += t.fmm->p2p_pairs * (t.fmm->nc_kind == 2 ? 8 : 4) + t.fmm->N * 8;
+        if (t.fmm->nc_kind) held += t.fmm->near_cache_bytes(t.fmm->nc_kind == 2);
     int64_t budget = near_budget;
-    if (budget < 0) {
+    if (budget < 0) {   // what is free (with the caches held) less a reserve for later work
       size_t fr = 0, tot = 0;
       YQ_HIP(hipMemGetInfo(&fr, &tot));
-      budget = ((int64_t)fr + held) / 2;
+      const int64_t reserve = std::max<int64_t>((int64_t)8 << 30, (int64_t)tot / 10);
+      budget = std::max<int64_t>(0, (int64_t)fr + held - reserve);
     }
     int64_t used = 0;
     near_trees32 = near_trees64 = 0;
@@ -880,7 +905,7 @@ void Engine::rebuild() {
       const bool f64 = pass == 1;
       for (auto& t : f64 ? thi : tin) {
         const int want = f64 ? 2 : 1;
-        const int64_t need = t.fmm->p2p_pairs * (f64 ? 8 : 4) + t.fmm->N * 8;
+        const int64_t need = t.fmm->near_cache_bytes(f64);
         if (used + need <= budget) {
           if (t.fmm->nc_kind != want) t.fmm->build_near_cache(f64, t.tab, stream);
           used += need;
@@ -940,12 +965,6 @@ void Engine::rebuild() {
     fill_int_kernel<<<nb256(std::max(nc, 1)), 256, 0, stream>>>(conv.p, std::max(nc, 1), 0);
     YQ_HIP(hipGetLastError());
   }
-  V.reserve((size_t)(m + 1) * std::max<int64_t>(T, 1));
-  w.reserve(std::max<int64_t>(T, 1));
-  r.reserve(std::max<int64_t>(T, 1));
-  tmp.reserve(std::max<int64_t>(T, 1));
-  delta.reserve(std::max<int64_t>(T, 1));
-  f.reserve(std::max<int64_t>(T, 1));
   drop_graphs();
   YQ_HIP(hipStreamSynchronize(stream));
 }

@@ -369,8 +369,9 @@ __device__ __forceinline__ void far_fused64_class_tile(int cls, double xi, doubl
 }
 
 // Window + extra-near correction of target i (local index) for density sg.
+template <class TW>
 __device__ __forceinline__ double correction_row(int64_t i, int64_t N, int P, int win,
-                                                 const double* __restrict__ W,
+                                                 const TW* __restrict__ W,
                                                  const int* __restrict__ xrow,
                                                  const int* __restrict__ xpan,
                                                  const double* __restrict__ xvals,
@@ -383,9 +384,9 @@ __device__ __forceinline__ double correction_row(int64_t i, int64_t N, int P, in
     int kj = (k + sl - win) % P;
     if (kj < 0) kj += P;
     const double* sg = sigma + (pid * P + kj) * Q;
-    const double* wr = W + (int64_t)sl * Q * N + i;
+    const TW* wr = W + (int64_t)sl * Q * N + i;
 #pragma unroll
-    for (int m = 0; m < Q; ++m) corr = fma(wr[(int64_t)m * N], sg[m], corr);
+    for (int m = 0; m < Q; ++m) corr = fma((double)wr[(int64_t)m * N], sg[m], corr);
   }
   if (xvals)
     for (int e = xrow[i]; e < xrow[i + 1]; ++e) {

@@ -64,6 +64,9 @@ struct Fmm {
   DevBuf<double> nc64;                // FP64 coefficients (the FP64 leaf pass)
   int nc_kind = 0;                    // 0 none, 1 FP32, 2 FP64
   DevBuf<double> ss;                  // the density in sorted node order (cached passes)
+  // P2M coefficients (with the FP32 cache): M_n of a leaf = sum over its sorted nodes
+  // k of sigma_k pc32[k 2 (p + 1) + 2 n + (0: re, 1: im)]
+  DevBuf<float> pc32;
   DevBuf<double2> tg;  // M2M / L2L tables: [level][cpos 0..3][k + 2p], k in -2p..2p
   DevBuf<double2> ts;  // M2L tables: [level][offset 0..48][k + 2p]
   int max_leaf = 0;
@@ -121,6 +124,10 @@ struct Fmm {
   // geometry; p2p_pairs x 8 (or 4) bytes.  drop_near_cache frees it.
   void build_near_cache(bool f64, const double* tab, hipStream_t s);
   void drop_near_cache();
+  // device bytes build_near_cache(f64) takes
+  int64_t near_cache_bytes(bool f64) const {
+    return p2p_pairs * (f64 ? 8 : 4) + N * 8 + (f64 ? 0 : N * 2 * (p + 1) * 4);
+  }
 };
 
 // One tree of an FMM forest as the forest kernels see it (device copy): the
@@ -137,6 +144,7 @@ struct FmmDev {
   const void* nc;
   int nc_kind;
   double* ss;
+  const float* pc32;       // P2M coefficients (FP32 cache), or null
   double kappa;
   const int* perm;
   const double *xs, *ys, *wnxs, *wnys;

@@ -263,6 +263,10 @@ constexpr int FB = 64;
 // the wave sums each coefficient; lane n keeps M_n.  Leaf b's coefficients go to
 // box gid[b] of M.
 // itab: [(p + 2) * 64] doubles of LDS (scaled I_n, one column per lane) when use_col.
+// COEF: instead of the sums, write each node's terms for unit density (qx, qy = the
+// nodes' w nu) times kappa / 4 pi to coef[k 2 (p + 1) + 2 n + (re, im)] (FP32), the
+// P2M coefficients of the cached pass.
+template <bool COEF = false>
 __device__ __forceinline__ void p2m_leaf(int b, int p, int use_col, double kappa,
                                          const int* __restrict__ ls, const int* __restrict__ lc,
                                          const int* __restrict__ gid,
@@ -272,7 +276,7 @@ __device__ __forceinline__ void p2m_leaf(int b, int p, int use_col, double kappa
                                          const double* __restrict__ ys,
                                          const double* __restrict__ qx,
                                          const double* __restrict__ qy, double2* __restrict__ M,
-                                         double* itab) {
+                                         double* itab, float* __restrict__ coef = nullptr) {
   const int lane = threadIdx.x;
   const int s0 = as_k(ls)[b], cnt = as_k(lc)[b];
   const double cx = as_k(ccx)[b], cy = as_k(ccy)[b];
@@ -302,11 +306,20 @@ __device__ __forceinline__ void p2m_leaf(int b, int p, int use_col, double kappa
       const double2 gp = make_double2(Ip * Ep.x, -Ip * Ep.y);            // conj(g_{n+1})
       double2 c = cmul(Qc, gm);
       c = cmad(Q, gp, c);
-      c.x = wave_sum(c.x);
-      c.y = wave_sum(c.y);
-      if (lane == n) {
-        mine.x += c.x;
-        mine.y += c.y;
+      if (COEF) {
+        if (j < cnt) {
+          const double sc = kappa / (4.0 * PI);
+          const int64_t a = (int64_t)(s0 + j) * 2 * (p + 1) + 2 * n;
+          as_gm(coef)[a] = (float)(c.x * sc);
+          as_gm(coef)[a + 1] = (float)(c.y * sc);
+        }
+      } else {
+        c.x = wave_sum(c.x);
+        c.y = wave_sum(c.y);
+        if (lane == n) {
+          mine.x += c.x;
+          mine.y += c.y;
+        }
       }
       pref *= hx * recip(n + 2);
       Im = I0;
@@ -317,10 +330,40 @@ __device__ __forceinline__ void p2m_leaf(int b, int p, int use_col, double kappa
       Ep = cmul(Ep, e1);
     }
   }
-  if (lane <= p) {
+  if (!COEF && lane <= p) {
     const double sc = kappa / (4.0 * PI);
     M[(int64_t)gid[b] * (p + 1) + lane] = make_double2(mine.x * sc, mine.y * sc);
   }
+}
+
+// M_n of leaf b from the P2M coefficients and the sorted densities: one wave, lane m
+// < 2 (p + 1) sums component m over the leaf's nodes in order (FP32 products and sums,
+// the inner operator's precision).
+__device__ __forceinline__ void p2m_cached_leaf(int b, int p, const int* __restrict__ ls,
+                                                const int* __restrict__ lc,
+                                                const int* __restrict__ gid,
+                                                const float* __restrict__ coef,
+                                                const double* __restrict__ ssd,
+                                                double2* __restrict__ M) {
+  constexpr int CB = 8;
+  const int lane = threadIdx.x % FB;
+  const int s0 = as_k(ls)[b], cnt = as_k(lc)[b];
+  const int R = 2 * (p + 1);
+  const int m = lane < R ? lane : 0;
+  const gptr<float> cb = as_g(coef + (int64_t)s0 * R + m);
+  float acc = 0.0f;
+  for (int j0 = 0; j0 < cnt; j0 += CB) {
+    float c[CB], sv[CB];
+#pragma unroll
+    for (int v = 0; v < CB; ++v) {
+      const int jc = min(j0 + v, cnt - 1);
+      c[v] = cb[(int64_t)jc * R];
+      sv[v] = (float)as_k(ssd)[s0 + jc];
+    }
+#pragma unroll
+    for (int v = 0; v < CB; ++v) acc = fmaf(j0 + v < cnt ? c[v] : 0.0f, sv[v], acc);
+  }
+  if (lane < R) as_gm(reinterpret_cast<double*>(M))[(int64_t)as_k(gid)[b] * R + lane] = (double)acc;
 }
 
 __global__ __launch_bounds__(64) void p2m_kernel(int p, int use_col, double kappa,
@@ -1916,6 +1959,22 @@ __global__ __launch_bounds__(64) void near_cache_kernel(
   }
 }
 
+__global__ __launch_bounds__(64) void p2m_coef_kernel(int p, int use_col, double kappa,
+                                                      const int* __restrict__ ls,
+                                                      const int* __restrict__ lc,
+                                                      const int* __restrict__ gid,
+                                                      const double* __restrict__ ccx,
+                                                      const double* __restrict__ ccy,
+                                                      const double* __restrict__ xs,
+                                                      const double* __restrict__ ys,
+                                                      const double* __restrict__ wnxs,
+                                                      const double* __restrict__ wnys,
+                                                      float* __restrict__ coef) {
+  extern __shared__ double itab[];
+  p2m_leaf<true>(blockIdx.x, p, use_col, kappa, ls, lc, gid, ccx, ccy, xs, ys, wnxs, wnys, nullptr,
+                 itab, coef);
+}
+
 void Fmm::build_near_cache(bool f64, const double* tab, hipStream_t s) {
   YQ_REQUIRE(nleaf > 0 && blk_off.p, YQ_ESTATE, "FMM tree not built");
   drop_near_cache();
@@ -1933,6 +1992,14 @@ void Fmm::build_near_cache(bool f64, const double* tab, hipStream_t s) {
   k<<<nleaf, 64, 0, s>>>(leaf_start.p, leaf_cnt.p, nbp.p, nbi.p, blk_off.p, xs.p, ys.p, wnxs.p,
                          wnys.p, kappa, tab, out);
   YQ_HIP(hipGetLastError());
+  if (!f64) {   // the inner operator's P2M coefficients
+    pc32.fit((size_t)std::max<int64_t>(N, 1) * 2 * (p + 1));
+    const int col = p <= kColMaxOrder;
+    p2m_coef_kernel<<<nleaf, 64, col ? (size_t)(p + 2) * 64 * sizeof(double) : 0, s>>>(
+        p, col, kappa, leaf_start.p, leaf_cnt.p, leaf_gid.p, leaf_cx.p, leaf_cy.p, xs.p, ys.p,
+        wnxs.p, wnys.p, pc32.p);
+    YQ_HIP(hipGetLastError());
+  }
   nc_kind = f64 ? 2 : 1;
 }
 
@@ -1940,6 +2007,7 @@ void Fmm::drop_near_cache() {
   nc32.release();
   nc64.release();
   ss.release();
+  pc32.release();
   nc_kind = 0;
 }
 
@@ -1980,6 +2048,10 @@ __global__ __launch_bounds__(64) void forest_p2m_kernel(const FmmDev* __restrict
   const int2 it = items[blockIdx.x];
   const FmmDev& d = fd[it.x];
   if (!mask[d.cfg]) return;
+  if (d.pc32) {
+    p2m_cached_leaf(it.y, p, d.leaf_start, d.leaf_cnt, d.leaf_gid, d.pc32, d.ss, d.Mall);
+    return;
+  }
   p2m_leaf(it.y, p, use_col, d.kappa, d.leaf_start, d.leaf_cnt, d.leaf_gid, d.leaf_cx, d.leaf_cy,
            d.xs, d.ys, d.qx, d.qy, d.Mall, itab);
 }
@@ -2162,6 +2234,7 @@ void FmmForest::build(const std::vector<Tree>& trees, bool p2p32, hipStream_t s)
     d.nc = cached ? (p2p32 ? (const void*)f.nc32.p : (const void*)f.nc64.p) : nullptr;
     d.nc_kind = cached ? f.nc_kind : 0;
     d.ss = cached ? f.ss.p : nullptr;
+    d.pc32 = cached && p2p32 && f.pc32.p ? f.pc32.p : nullptr;
     d.Mall = f.Mall.p;
     d.Lall = f.Lall.p;
     d.lv = f.m2l_levels();

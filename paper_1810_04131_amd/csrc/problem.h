@@ -48,6 +48,8 @@ struct yq_problem {
   int64_t x_total = 0;
   DevBuf<double> xvals, xgvals;
   DevBuf<double> W, WGx, WGy;
+  DevBuf<float> W32;   // W rounded to FP32 (the batch engine's inner operator)
+  const double* W32_src = nullptr;   // the W it was rounded from
   DevBuf<double> Lqbx, Lnear, Lpot, tab;
   Consts consts{};
   FarPlan fp{};

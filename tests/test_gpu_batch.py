@@ -252,11 +252,12 @@ def test_batch_fmm_forest_matches_oracle_single_path_and_alone(oracles):
         assert infos[c]["residual"] <= 1e-10, (c, infos[c])
         assert _rel(sig[s], o["sigma"]) < 1e-8, c
         if c in (2, 4):
-            # forest trees: the inner operator is the standalone FMM problem's, and
-            # the FP64 one the order-40 FMM's (operator error ~1e-10)
+            # forest trees: the inner operator is the standalone FMM problem's up to the
+            # engine's FP32 copy of the QBX correction, and the FP64 one the order-40
+            # FMM's (operator error ~1e-10)
             pb = yq.Problem(yq.default_params(far_mode=yq.YQ_FAR_FMM, **prm))
             pb.set_workload(cfgs[c])
-            assert _rel(op32[s], _np(pb.apply_operator(x[s], yq.YQ_MIXED))) < 1e-13, c
+            assert _rel(op32[s], _np(pb.apply_operator(x[s], yq.YQ_MIXED))) < 1e-6, c
             assert _rel(op64[s], o["A"] @ x[s]) < 1e-9, c
             pb.set_boundary_data(pb.boundary_label())
             ss, _ = pb.solve()
