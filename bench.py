@@ -109,6 +109,7 @@ PH_FAR64, PH_FAR32 = 0, 1   # profiling phases of the library (yq_profile_enable
 PH_QBX, PH_FUSED, PH_REPULSION = 4, 6, 7
 COUNTERS_FILE = "profiles/far32_kernel_50ellipses_N25600_counters.txt"
 PEAK_FP32 = 157.3e12   # published MI355X FP32 vector peak (needs packed FP32)
+PEAK_HBM = 8.0e12      # published MI355X HBM3E bandwidth (bytes/s)
 PEAK_FP64 = 78.6e12    # published MI355X FP64 vector peak
 
 
@@ -213,7 +214,7 @@ def batch_counters(kind):
     return _kv_counters(BATCH_COUNTERS_FILE[kind], BATCH_SRC)
 
 
-LEAF_COUNTERS_FILE = "profiles/forest_leaf_kernel_batch_counters.txt"
+LEAF_COUNTERS_FILE = "profiles/forest_cleaf_kernel_batch_counters.txt"
 LEAF_SRC = ["paper_1810_04131_amd/csrc/fmm.hip", "paper_1810_04131_amd/csrc/farfield_core.h",
             "paper_1810_04131_amd/csrc/bessel.h", "paper_1810_04131_amd/csrc/bessel_tables.h"]
 
@@ -478,8 +479,8 @@ def bench_batch(args):
     t_all = time.perf_counter() - t_all
     n32, ms32, pairs32 = b.profile_read(yq.YQ_MIXED)
     n64, ms64, pairs64 = b.profile_read(yq.YQ_FP64)
-    nl32, msl32, pairsl32 = b.profile_read(yq.YQ_MIXED, kernel="leaf")
-    nl64, msl64, pairsl64 = b.profile_read(yq.YQ_FP64, kernel="leaf")
+    nl32, msl32, pairsl32, bytesl32 = b.profile_read(yq.YQ_MIXED, kernel="leaf")
+    nl64, msl64, pairsl64, bytesl64 = b.profile_read(yq.YQ_FP64, kernel="leaf")
     its = np.array([i["iterations"] for i in infos])
     ref = np.array([i["outer_steps"] for i in infos])
     mv = np.array([i["matvecs_fp32"] + i["matvecs_fp64"] for i in infos], dtype=float)
@@ -554,24 +555,30 @@ def bench_batch(args):
                                if "valu_flops_per_pair" in bc and ms32 > 0 else None),
               "pairs_per_launch": pairs32 / max(n32, 1), "avg_launch_ms": avg32,
               "launches": n32, "total_ms": ms32}
-    # the forest's FP32 leaf pass (both launches of an operator application, bracketed
-    # together): 40 flop per directed pair of its direct interactions, the pair's
-    # general FP32 path (every pair of neighbouring leaves takes it); the FP64 local
-    # expansion evaluated at each target in the same launches is not counted
+    # the forest's FP32 leaf pass (its launches of one operator application bracketed
+    # together).  With the near-field caches it reads stored coefficients: HBM-bound,
+    # achieved = the algorithmic bytes the launches report (4 per pair, 16 per target,
+    # 8 per source of each list entry) / their time.  Without them it evaluates K1 per
+    # pair: 40 flop per directed pair (the general FP32 path)
     lc = leaf_counters()
-    ach_l = 40.0 * pairsl32 / (msl32 * 1e-3) if msl32 > 0 else 0.0
-    leaf = {"bound": "alu", "kernel": "forest_leaf_kernel", "achieved": ach_l / 1e12,
-            "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s", "frac": ach_l / PEAK_FP32,
-            "traffic": (lc["hbm_bytes_per_pair"] * pairsl32 / max(nl32, 1)
-                        if "hbm_bytes_per_pair" in lc else None),
-            "flops_per_pair": 40.0,
-            "counter_flops_per_pair": lc.get("valu_flops_per_pair"),
-            "counter_frac": (lc["valu_flops_per_pair"] * pairsl32 / (msl32 * 1e-3) / PEAK_FP32
-                             if "valu_flops_per_pair" in lc and msl32 > 0 else None),
-            "pairs_per_launch": pairsl32 / max(nl32, 1),
-            "avg_launch_ms": msl32 / max(nl32, 1), "launches": nl32, "total_ms": msl32,
-            "launch_note": "one timed launch = the leaf pass of one operator application "
-                           "(its two launches: leaves served by 2 and by 4 wavefronts)"}
+    if bytesl32 > 0:
+        ach_l = bytesl32 / (msl32 * 1e-3) / 1e9 if msl32 > 0 else 0.0
+        leaf = {"bound": "hbm", "kernel": "forest_cleaf_kernel", "achieved": ach_l,
+                "peak": PEAK_HBM / 1e9, "unit": "GB/s", "frac": ach_l * 1e9 / PEAK_HBM,
+                "traffic": (lc["hbm_bytes_per_pair"] * pairsl32 / max(nl32, 1)
+                            if "hbm_bytes_per_pair" in lc else None),
+                "bytes_per_launch": bytesl32 / max(nl32, 1),
+                "bytes_per_pair": bytesl32 / max(pairsl32, 1)}
+    else:
+        ach_l = 40.0 * pairsl32 / (msl32 * 1e-3) if msl32 > 0 else 0.0
+        leaf = {"bound": "alu", "kernel": "forest_leaf_kernel", "achieved": ach_l / 1e12,
+                "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s", "frac": ach_l / PEAK_FP32,
+                "traffic": None, "flops_per_pair": 40.0}
+    leaf.update({"pairs_per_launch": pairsl32 / max(nl32, 1),
+                 "avg_launch_ms": msl32 / max(nl32, 1), "launches": nl32, "total_ms": msl32,
+                 "launch_note": "one timed launch = the leaf pass of one operator application "
+                                "(the local expansions' evaluation at the nodes runs before it, "
+                                "outside the bracket)"})
     fp64 = {"direct_kernel": {"kernel": "bfar64_kernel", "launches": n64,
                               "avg_launch_ms": ms64 / max(n64, 1),
                               "achieved": F64_ALG * pairs64 / (ms64 * 1e-3) / 1e12
@@ -579,9 +586,12 @@ def bench_batch(args):
                               "peak": PEAK_FP64 / 1e12,
                               "frac": F64_ALG * pairs64 / (ms64 * 1e-3) / PEAK_FP64
                               if ms64 > 0 else None},
-            "forest_leaf": {"kernel": "forest_leaf_kernel (FP64 pairs)", "launches": nl64,
-                            "avg_launch_ms": msl64 / max(nl64, 1),
-                            "pairs_per_launch": pairsl64 / max(nl64, 1)}}
+            "forest_leaf": {"kernel": "forest_cleaf_kernel / forest_leaf_kernel (FP64)",
+                            "launches": nl64, "avg_launch_ms": msl64 / max(nl64, 1),
+                            "pairs_per_launch": pairsl64 / max(nl64, 1),
+                            "bytes_per_launch": bytesl64 / max(nl64, 1),
+                            "achieved_GBps": (bytesl64 / (msl64 * 1e-3) / 1e9
+                                              if msl64 > 0 and bytesl64 > 0 else None)}}
     # the dominant FP32 kernel of the timed steps carries the roofline
     if msl32 > ms32:
         roof = dict(leaf, other_fp32_kernel=direct if n32 and pairs32 else None, fp64=fp64)
@@ -627,6 +637,8 @@ def bench_batch(args):
         "matvec_interactions_per_s_fp32": (pairs32 / (ms32 * 1e-3) if ms32 > 0 and pairs32 > 0
                                            else None),
         "leaf_pass_interactions_per_s_fp32": pairsl32 / (msl32 * 1e-3) if msl32 > 0 else None,
+        "leaf_pass_cached_GBps_fp32": (bytesl32 / (msl32 * 1e-3) / 1e9
+                                       if msl32 > 0 and bytesl32 > 0 else None),
         "matvec_interactions_per_s_fp64": (pairs64 / (ms64 * 1e-3) if ms64 > 0 and pairs64 > 0
                                            else None),
         "fp64_one_at_a_time": {"sample": len(sample), "of": len(cfgs),

@@ -444,13 +444,18 @@ int yq_batch_use_graphs(yq_batch* batch, int32_t enable);
  * pass counts the pairs of every leaf with the leaves of its direct-interaction
  * list).  yq_batch_profile_read (direct far field) and yq_batch_profile_read_leaf
  * (leaf pass) synchronise and return, for YQ_MIXED or YQ_FP64, the number of
- * timed launches, their summed duration (ms) and the summed pairs; reset != 0
- * clears them.  Configurations of the FMM lane are not counted.  All synchronous. */
+ * timed launches, their summed duration (ms) and the summed pairs; the leaf pass
+ * also the algorithmic bytes of its trees that read a near-field cache
+ * (coefficients once, each target's output read and written, each list entry's
+ * source densities once; bytes may be NULL); reset != 0 clears them.  The leaf
+ * pass's timer does not include the local expansions' evaluation at the nodes,
+ * which runs before it.  Configurations of the FMM lane are not counted.  All
+ * synchronous. */
 int yq_batch_profile_enable(yq_batch* batch, int32_t enable);
 int yq_batch_profile_read(yq_batch* batch, int32_t precision, int64_t* launches,
                           double* total_ms, double* pairs, int32_t reset);
 int yq_batch_profile_read_leaf(yq_batch* batch, int32_t precision, int64_t* launches,
-                               double* total_ms, double* pairs, int32_t reset);
+                               double* total_ms, double* pairs, double* bytes, int32_t reset);
 
 /* ---- Serving -----------------------------------------------------------------------------
  * A continuous-batching solve server on one GPU.  Requests (one particle

@@ -402,12 +402,18 @@ class Batch:
     def profile_read(self, precision=YQ_MIXED, reset=True, kernel="direct"):
         """(launches, total ms, source-target pairs) of the timed far-field launches:
         kernel "direct" (the direct members' fused far field) or "leaf" (the FMM
-        forest's leaf pass)."""
-        fn = {"direct": self.lib.yq_batch_profile_read,
-              "leaf": self.lib.yq_batch_profile_read_leaf}[kernel]
-        n, ms, pairs = ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
-        self._check(fn(self.h, int(precision), ctypes.byref(n), ctypes.byref(ms),
-                       ctypes.byref(pairs), int(bool(reset))))
+        forest's leaf pass; then also the algorithmic bytes of its cached trees)."""
+        n, ms, pairs, by = ctypes.c_int64(), ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        if kernel == "leaf":
+            self._check(self.lib.yq_batch_profile_read_leaf(
+                self.h, int(precision), ctypes.byref(n), ctypes.byref(ms), ctypes.byref(pairs),
+                ctypes.byref(by), int(bool(reset))))
+            return int(n.value), float(ms.value), float(pairs.value), float(by.value)
+        if kernel != "direct":
+            raise KeyError(kernel)
+        self._check(self.lib.yq_batch_profile_read(self.h, int(precision), ctypes.byref(n),
+                                                   ctypes.byref(ms), ctypes.byref(pairs),
+                                                   int(bool(reset))))
         return int(n.value), float(ms.value), float(pairs.value)
 
     def segment(self, v, c):

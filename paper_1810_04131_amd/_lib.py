@@ -144,7 +144,7 @@ SIGNATURES = {
                                         ctypes.POINTER(c_double), c_int32]),
     "yq_batch_profile_read_leaf": (c_int32, [P, c_int32, ctypes.POINTER(c_int64),
                                              ctypes.POINTER(c_double), ctypes.POINTER(c_double),
-                                             c_int32]),
+                                             ctypes.POINTER(c_double), c_int32]),
     "yq_server_create": (c_int32, [ctypes.POINTER(yq_params), c_int64, c_int32, c_double,
                                    ctypes.POINTER(c_void_p)]),
     "yq_server_destroy": (None, [P]),

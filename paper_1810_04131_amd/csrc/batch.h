@@ -108,7 +108,7 @@ struct Engine {
   bool prof_on = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev[2][2];
   std::vector<hipEvent_t> ev_pool;
-  DevBuf<unsigned long long> prof_pairs;   // [precision * 2 + kind]
+  DevBuf<unsigned long long> prof_pairs;   // [(precision * 2 + kind) * 2 + (pairs, bytes)]
   unsigned long long* prof_counter(int prec, int kind) const;
   void prof_record(int prec, int kind, hipEvent_t a, hipEvent_t b);
 
@@ -123,7 +123,8 @@ struct Engine {
   void drop_graphs();
   hipEvent_t prof_event();
   void set_profiling(bool on);
-  void read_profile(int prec, int kind, int64_t& launches, double& ms, double& pairs, bool reset);
+  void read_profile(int prec, int kind, int64_t& launches, double& ms, double& pairs,
+                    double& bytes, bool reset);
   void dots(const int* mask, const double* x, const double* y);
   void axpby(const int* mask, double a, const double* x, double b, const double* y, double* out);
   void iteration(int prec);

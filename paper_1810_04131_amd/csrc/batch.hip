@@ -975,7 +975,7 @@ int Engine::grid_blocks(int n) const {
 }
 
 unsigned long long* Engine::prof_counter(int prec, int kind) const {
-  return prof_on ? prof_pairs.p + 2 * (prec == YQ_MIXED ? 1 : 0) + kind : nullptr;
+  return prof_on ? prof_pairs.p + 2 * (2 * (prec == YQ_MIXED ? 1 : 0) + kind) : nullptr;
 }
 
 void Engine::prof_record(int prec, int kind, hipEvent_t a, hipEvent_t b) {
@@ -995,6 +995,7 @@ void Engine::matvec_part(int part, int prec, const int* mask, const double* Vin,
       bpack32_kernel<<<nb256(T), 256, 0, stream>>>(conf.p, node_conf.p, T, mask, Vin, col,
                                                    sym32 ? 1 : 0);
     fo.expansions(mask, Vin, col, T, stream);
+    fo.l2p(mask, stream);
   } else if (part == PART_LEAF) {
     fo.leaves(mask, stream, prof_counter(prec, PK_LEAF));
   } else if (part == PART_DIRECT) {
@@ -1167,14 +1168,14 @@ void Engine::set_profiling(bool on) {
   drop_graphs();   // the captured sequence changes with the timers
   prof_on = on;
   if (on && !prof_pairs.p) {
-    prof_pairs.alloc(4);
-    YQ_HIP(hipMemsetAsync(prof_pairs.p, 0, 4 * sizeof(unsigned long long), stream));
+    prof_pairs.alloc(8);
+    YQ_HIP(hipMemsetAsync(prof_pairs.p, 0, 8 * sizeof(unsigned long long), stream));
     YQ_HIP(hipStreamSynchronize(stream));
   }
 }
 
 void Engine::read_profile(int prec, int kind, int64_t& launches, double& ms, double& pairs,
-                          bool reset) {
+                          double& bytes, bool reset) {
   const int gi = prec == YQ_MIXED ? 1 : 0;
   auto& ev = prof_ev[gi][kind];
   YQ_HIP(hipStreamSynchronize(stream));
@@ -1185,10 +1186,12 @@ void Engine::read_profile(int prec, int kind, int64_t& launches, double& ms, dou
     YQ_HIP(hipEventElapsedTime(&t, e.first, e.second));
     ms += t;
   }
-  unsigned long long pc[4] = {0, 0, 0, 0};
+  unsigned long long pc[8] = {};
   if (prof_pairs.p)
-    YQ_HIP(hipMemcpy(pc, prof_pairs.p, 4 * sizeof(unsigned long long), hipMemcpyDeviceToHost));
-  pairs = (double)pc[2 * gi + kind];
+    YQ_HIP(hipMemcpy(pc, prof_pairs.p, 8 * sizeof(unsigned long long), hipMemcpyDeviceToHost));
+  const int slot = 2 * (2 * gi + kind);
+  pairs = (double)pc[slot];
+  bytes = (double)pc[slot + 1];
   if (reset) {
     for (auto& e : ev) {
       ev_pool.push_back(e.first);
@@ -1196,7 +1199,7 @@ void Engine::read_profile(int prec, int kind, int64_t& launches, double& ms, dou
     }
     ev.clear();
     if (prof_pairs.p) {
-      YQ_HIP(hipMemsetAsync(prof_pairs.p + 2 * gi + kind, 0, sizeof(unsigned long long), stream));
+      YQ_HIP(hipMemsetAsync(prof_pairs.p + slot, 0, 2 * sizeof(unsigned long long), stream));
       YQ_HIP(hipStreamSynchronize(stream));
     }
   }
@@ -1404,6 +1407,7 @@ void Engine::resid(const std::vector<int>& plain, const std::vector<int>& fused,
   upload_mask(pmask, plain);
   upload_mask(fmask, fused);
   forest_hi.expansions(inc.p, x, nullptr, T, stream);
+  forest_hi.l2p(inc.p, stream);
   {
     hipEvent_t a = prof_on ? prof_event() : nullptr;
     if (a) YQ_HIP(hipEventRecord(a, stream));

@@ -440,29 +440,30 @@ int yq_batch_profile_enable(yq_batch* b, int32_t enable) {
 
 namespace {
 int profile_read(yq_batch* b, int kind, int32_t precision, int64_t* launches, double* total_ms,
-                 double* pairs, int32_t reset) {
+                 double* pairs, double* bytes, int32_t reset) {
   return bguard(b, [&] {
     YQ_REQUIRE(b && launches && total_ms && pairs, YQ_EINVAL, "null argument");
     YQ_REQUIRE(precision == YQ_FP64 || precision == YQ_MIXED, YQ_EINVAL, "bad precision");
     int64_t n = 0;
-    double ms = 0.0, pc = 0.0;
+    double ms = 0.0, pc = 0.0, by = 0.0;
     if (b->eng.prof_on || !b->eng.prof_ev[precision == YQ_MIXED ? 1 : 0][kind].empty())
-      b->eng.read_profile(precision, kind, n, ms, pc, reset != 0);
+      b->eng.read_profile(precision, kind, n, ms, pc, by, reset != 0);
     *launches = n;
     *total_ms = ms;
     *pairs = pc;
+    if (bytes) *bytes = by;
   });
 }
 }  // namespace
 
 int yq_batch_profile_read(yq_batch* b, int32_t precision, int64_t* launches, double* total_ms,
                           double* pairs, int32_t reset) {
-  return profile_read(b, PK_DIRECT, precision, launches, total_ms, pairs, reset);
+  return profile_read(b, PK_DIRECT, precision, launches, total_ms, pairs, nullptr, reset);
 }
 
 int yq_batch_profile_read_leaf(yq_batch* b, int32_t precision, int64_t* launches,
-                               double* total_ms, double* pairs, int32_t reset) {
-  return profile_read(b, PK_LEAF, precision, launches, total_ms, pairs, reset);
+                               double* total_ms, double* pairs, double* bytes, int32_t reset) {
+  return profile_read(b, PK_LEAF, precision, launches, total_ms, pairs, bytes, reset);
 }
 
 int yq_batch_use_graphs(yq_batch* b, int32_t enable) {

@@ -53,6 +53,7 @@ struct Fmm {
   DevBuf<int> nbp, nbi;               // P2P leaves (CSR, self included): every leaf whose
                                       // ancestor at the coarser of the two levels is adjacent
   int64_t p2p_pairs = 0;              // source-target pairs of one P2P pass
+  int64_t p2p_srcs = 0;               // sum over the P2P entries of their source counts
   int64_t m2l_pairs = 0;              // box pairs of one M2L pass
   // Near-field cache: the leaf pass's pair coefficients K1(z)/z ((x - y) . w nu) for
   // this geometry, so that the pass reads them instead of evaluating them.  Entry e
@@ -139,6 +140,7 @@ struct FmmDev {
   int depth, nleaf;
   int64_t N, off;          // nodes; offset of the configuration in the batch vectors
   int64_t p2p_pairs;       // source-target pairs of one leaf pass
+  int64_t p2p_srcs;        // sum over its P2P entries of their source counts
   const int64_t* blk_off;  // near-field cache (nc_kind 1: float, 2: double; 0: none)
   const int2* ent;
   const void* nc;
@@ -208,7 +210,12 @@ struct FmmForest {
   // passes after them: far field (leaves) or its gradient (leaves_grad, FP64 forests)
   void expansions(const int* mask, const double* V, const int* col, int64_t T,
                   hipStream_t s) const;
-  // pairs (may be null): adds the source-target pairs the leaf pass evaluates
+  // the local expansions' values at the nodes (out = L2P), then the leaf pass adds the
+  // direct interactions.  pairs (may be null): adds the source-target pairs the leaf
+  // pass evaluates and, into pairs[1], the algorithmic bytes of its cached trees
+  // (coefficients once, each target's output read and written, each entry's source
+  // densities once)
+  void l2p(const int* mask, hipStream_t s) const;
   void leaves(const int* mask, hipStream_t s, unsigned long long* pairs = nullptr) const;
   void leaves_grad(const int* mask, hipStream_t s) const;
 };

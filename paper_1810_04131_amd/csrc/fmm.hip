@@ -1567,6 +1567,8 @@ void Fmm::build(int64_t n, double kap, int order, int lmax, const double* tab, h
   depth = t.depth;
   max_leaf = t.max_leaf;
   p2p_pairs = t.p2p_pairs;
+  p2p_srcs = 0;
+  for (size_t e = 0; e < t.nbi.size(); ++e) p2p_srcs += t.leaf_cnt[t.nbi[e]];
   lv.resize(depth + 1);   // levels keep their device buffers from earlier builds
   nbox_total = 0;
   m2l_pairs = 0;
@@ -1726,6 +1728,7 @@ void Fmm::copy_tree(const Fmm& o, int q, const double* tab, hipStream_t s) {
   nbox_total = o.nbox_total;
   nleaf = o.nleaf;
   p2p_pairs = o.p2p_pairs;
+  p2p_srcs = o.p2p_srcs;
   m2l_pairs = o.m2l_pairs;
   lv.resize(o.lv.size());
   for (size_t l = 0; l < o.lv.size(); ++l) {
@@ -2142,22 +2145,37 @@ __global__ __launch_bounds__(256) void forest_l2p_kernel(const FmmDev* __restric
 }
 
 // Profiling: adds the source-target pairs of the leaf passes of the trees in mask
-// (each tree's count from its build) to *pairs.
+// (each tree's count from its build) to pairs[0], and the algorithmic bytes of the
+// cached trees' passes to pairs[1]: coefficients (4 or 8 bytes per pair), each
+// target's output read and written (16), each entry's source densities (8 per source).
 __global__ __launch_bounds__(256) void forest_count_pairs_kernel(const FmmDev* __restrict__ fd,
                                                                  int nmem,
                                                                  const int* __restrict__ mask,
+                                                                 int f32,
                                                                  unsigned long long* __restrict__ pairs) {
-  __shared__ unsigned long long part[256];
-  unsigned long long s = 0;
+  __shared__ unsigned long long part[2][256];
+  unsigned long long s = 0, by = 0;
   for (int m = threadIdx.x; m < nmem; m += blockDim.x)
-    if (mask[fd[m].cfg]) s += (unsigned long long)fd[m].p2p_pairs;
-  part[threadIdx.x] = s;
+    if (mask[fd[m].cfg]) {
+      const FmmDev& d = fd[m];
+      s += (unsigned long long)d.p2p_pairs;
+      if (d.nc)
+        by += (unsigned long long)(d.p2p_pairs * (f32 ? 4 : 8) + 16 * d.N + 8 * d.p2p_srcs);
+    }
+  part[0][threadIdx.x] = s;
+  part[1][threadIdx.x] = by;
   __syncthreads();
   for (int h = blockDim.x / 2; h > 0; h >>= 1) {
-    if ((int)threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
+    if ((int)threadIdx.x < h) {
+      part[0][threadIdx.x] += part[0][threadIdx.x + h];
+      part[1][threadIdx.x] += part[1][threadIdx.x + h];
+    }
     __syncthreads();
   }
-  if (threadIdx.x == 0) atomicAdd(pairs, part[0]);
+  if (threadIdx.x == 0) {
+    atomicAdd(pairs, part[0][0]);
+    atomicAdd(pairs + 1, part[1][0]);
+  }
 }
 
 __global__ __launch_bounds__(FB * PW) void forest_leaf_grad_kernel(const FmmDev* __restrict__ fd,
@@ -2227,6 +2245,7 @@ void FmmForest::build(const std::vector<Tree>& trees, bool p2p32, hipStream_t s)
     d.leaf_r = f.leaf_r.p;
     d.leaf_of = f.leaf_of.p;
     d.p2p_pairs = f.p2p_pairs;
+    d.p2p_srcs = f.p2p_srcs;
     // the tree's near-field cache when it holds this forest's precision
     const bool cached = p2p32 ? f.nc_kind == 1 : f.nc_kind == 2;
     d.blk_off = f.blk_off.p;
@@ -2303,12 +2322,18 @@ void FmmForest::build(const std::vector<Tree>& trees, bool p2p32, hipStream_t s)
 void FmmForest::apply(const int* mask, const double* V, const int* col, int64_t T,
                       hipStream_t s) const {
   expansions(mask, V, col, T, s);
+  l2p(mask, s);
   leaves(mask, s);
+}
+
+void FmmForest::l2p(const int* mask, hipStream_t s) const {
+  if (nmem == 0 || n_gather == 0) return;
+  forest_l2p_kernel<<<n_gather, 256, 0, s>>>(dev.p, it_gather.p, mask, p);
+  YQ_HIP(hipGetLastError());
 }
 
 void FmmForest::leaves(const int* mask, hipStream_t s, unsigned long long* pairs) const {
   if (nmem == 0) return;
-  if (n_gather) forest_l2p_kernel<<<n_gather, 256, 0, s>>>(dev.p, it_gather.p, mask, p);
   if (n_leaf2) {
     auto k = f32 ? forest_leaf_kernel<true, 2> : forest_leaf_kernel<false, 2>;
     k<<<n_leaf2, FB * 2, leaf_lds_bytes(2), s>>>(dev.p, it_leaf2.p, mask);
@@ -2321,7 +2346,7 @@ void FmmForest::leaves(const int* mask, hipStream_t s, unsigned long long* pairs
     auto k = f32 ? forest_cleaf_kernel<true> : forest_cleaf_kernel<false>;
     k<<<(n_cleaf + CW - 1) / CW, FB * CW, 0, s>>>(dev.p, it_cleaf.p, n_cleaf, mask);
   }
-  if (pairs) forest_count_pairs_kernel<<<1, 256, 0, s>>>(dev.p, nmem, mask, pairs);
+  if (pairs) forest_count_pairs_kernel<<<1, 256, 0, s>>>(dev.p, nmem, mask, f32, pairs);
   YQ_HIP(hipGetLastError());
 }
 

@@ -492,19 +492,20 @@ def test_batch_leaf_pass_timers_count_pairs_and_leave_results_unchanged():
     assert tree.sum() == 2
     x = np.random.default_rng(5).standard_normal(b.total)
     b.apply_operator(x, yq.YQ_MIXED)
-    n1, ms1, p1 = b.profile_read(yq.YQ_MIXED, reset=False, kernel="leaf")
+    n1, ms1, p1, by1 = b.profile_read(yq.YQ_MIXED, reset=False, kernel="leaf")
     b.apply_operator(x, yq.YQ_MIXED)
-    n2, ms2, p2 = b.profile_read(yq.YQ_MIXED, kernel="leaf")
+    n2, ms2, p2, _ = b.profile_read(yq.YQ_MIXED, kernel="leaf")
     assert n1 == 1 and n2 == 2 and 0.0 < ms1 < ms2 and p2 == 2 * p1
+    assert by1 == 0.0   # no near-field cache: no cached bytes
     assert float(N[tree].sum()) < p1 <= float((N[tree] ** 2).sum())
     b.apply_operator(x, yq.YQ_FP64)
-    n64, ms64, p64 = b.profile_read(yq.YQ_FP64, kernel="leaf")
+    n64, ms64, p64, _ = b.profile_read(yq.YQ_FP64, kernel="leaf")
     assert n64 == 1 and ms64 > 0.0 and p64 == p1
     b.set_boundary_data(b.boundary_label())
     s, infos = b.solve()
     assert np.array_equal(_np(s), _np(s_ref))
     assert [i["iterations"] for i in infos] == [i["iterations"] for i in i_ref]
-    n, ms, pairs = b.profile_read(yq.YQ_MIXED, kernel="leaf")
+    n, ms, pairs, _ = b.profile_read(yq.YQ_MIXED, kernel="leaf")
     assert n >= max(i["matvecs_fp32"] for i in infos) and 0 < pairs <= n * p1
 
 
@@ -520,6 +521,15 @@ def test_batch_near_cache_matches_uncached_leaf_passes():
     cached = _lane_batch(cfgs, True, near=-1, **prm)
     held, t32, t64 = cached.near_cache_info()
     assert (t32, t64) == (2, 2) and held > 0 and plain.near_cache_info() == (0, 0, 0)
+    # the cached pass's algorithmic bytes: 4 per pair, 16 per target, 8 per source of
+    # each list entry (at least one pair each, so at most 8 per pair)
+    cached.profile(True)
+    xp = np.random.default_rng(8).standard_normal(cached.total)
+    cached.apply_operator(xp, yq.YQ_MIXED)
+    _, _, pr, by = cached.profile_read(yq.YQ_MIXED, kernel="leaf")
+    Nt = float(np.diff(cached.offsets)[np.diff(cached.offsets) >= 5 * P * 16].sum())
+    assert 4 * pr + 16 * Nt < by <= 12 * pr + 16 * Nt
+    cached.profile(False)
     x = np.random.default_rng(9).standard_normal(cached.total)
     for prec, tol in ((yq.YQ_MIXED, 5e-6), (yq.YQ_FP64, 1e-12)):
         a = _np(cached.apply_operator(x, prec))
