@@ -152,6 +152,11 @@ def parse():
                     help="batch: inner far field of the direct members with one kernel "
                          "evaluation per unordered pair (bsym32_kernel) or per directed pair "
                          "(bfar32_kernel)")
+    ap.add_argument("--fmm-order", type=int, default=15,
+                    help="batch: inner FMM expansion order (default 15: with the order-40 FP64 "
+                         "residuals the mixed solves take the same iterations and refinement "
+                         "steps as at the library's 20, and 2 (p + 1) = 32 fills the MFMA "
+                         "operand tiles without padding; 0: the library's)")
     ap.add_argument("--near-cache-gb", type=float, default=None,
                     help="batch: device memory for the FMM trees' near-field caches (GB; 0 "
                          "none; default: the library's, the free memory less a reserve)")
@@ -439,6 +444,9 @@ def bench_batch(args):
     tol = args.tol
     prm = yq.default_params(panels_per_particle=32, qbx_order=10, tol=tol,
                             precision=yq.YQ_MIXED, restart=60, maxiter=300)
+    if args.fmm_order:
+        prm.fmm_order = args.fmm_order
+    inner_order = prm.fmm_order
     b = yq.Batch(prm)
     b.set_symmetric_far(args.far32 == "symmetric")
     if args.near_cache_gb is not None:
@@ -609,20 +617,21 @@ def bench_batch(args):
                                f"relative residual of {tol:g}; one step = batched solve + "
                                f"forces/torques of every configuration; "
                                + (f"every configuration a tree of the engine's FMM forest (FMM "
-                                  f"order 20 inner / 40 FP64 residuals), one graph-replayed "
+                                  f"order {inner_order} inner / 40 FP64 residuals; near-field "
+                                  f"caches), one graph-replayed "
                                   f"iteration for the whole batch; the forces of every "
                                   f"configuration in one batched pass" if forest and thr == 0
                                   else f"every configuration in the fused engine, one graph-replayed "
                                   f"iteration for the whole batch: {int((~lane).sum())} below "
                                   f"{thr} nodes with the fused direct far field, {int(lane.sum())} "
-                                  f"from {thr} nodes on as trees of the FMM forest (FMM order 20 "
-                                  f"inner / 40 FP64 residuals); the forces of every "
+                                  f"from {thr} nodes on as trees of the FMM forest (FMM order "
+                                  f"{inner_order} inner / 40 FP64 residuals); the forces of every "
                                   f"configuration in one batched pass" if forest
                                   else f"{int((~lane).sum())} configurations below {thr} nodes in the "
                                   f"fused direct engine (graph-replayed iteration), "
                                   f"{int(lane.sum())} from {thr} nodes on in the FMM lane "
-                                  f"({args.fmm_workers} workers, FMM order 20 inner / 40 FP64 "
-                                  f"residuals)" if hybrid
+                                  f"({args.fmm_workers} workers, FMM order {inner_order} inner / 40 "
+                                  f"FP64 residuals)" if hybrid
                                   else ("the configurations below %d nodes only, all in the fused "
                                         "direct engine" % min_nodes if engine_only
                                         else "every configuration in the fused direct engine")),
