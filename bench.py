@@ -153,10 +153,15 @@ def parse():
                          "evaluation per unordered pair (bsym32_kernel) or per directed pair "
                          "(bfar32_kernel)")
     ap.add_argument("--fmm-order", type=int, default=15,
-                    help="batch: inner FMM expansion order (default 15: with the order-40 FP64 "
+                    help="batch: inner FMM expansion order (default 15: with the FP64 "
                          "residuals the mixed solves take the same iterations and refinement "
                          "steps as at the library's 20, and 2 (p + 1) = 32 fills the MFMA "
                          "operand tiles without padding; 0: the library's)")
+    ap.add_argument("--fmm-resid-order", type=int, default=31,
+                    help="batch: order of the FP64 FMM of the refinement residuals and forces "
+                         "(default 31: its operator differs from the library's order 40 by "
+                         "1e-13 relative, far below the 1e-9 tolerance, and 2 (p + 1) = 64 "
+                         "fills the MFMA operand tiles; 0: the library's)")
     ap.add_argument("--near-cache-gb", type=float, default=None,
                     help="batch: device memory for the FMM trees' near-field caches (GB; 0 "
                          "none; default: the library's, the free memory less a reserve)")
@@ -446,7 +451,10 @@ def bench_batch(args):
                             precision=yq.YQ_MIXED, restart=60, maxiter=300)
     if args.fmm_order:
         prm.fmm_order = args.fmm_order
+    if args.fmm_resid_order:
+        prm.fmm_resid_order = args.fmm_resid_order
     inner_order = prm.fmm_order
+    resid_order = prm.fmm_resid_order
     b = yq.Batch(prm)
     b.set_symmetric_far(args.far32 == "symmetric")
     if args.near_cache_gb is not None:
@@ -617,7 +625,7 @@ def bench_batch(args):
                                f"relative residual of {tol:g}; one step = batched solve + "
                                f"forces/torques of every configuration; "
                                + (f"every configuration a tree of the engine's FMM forest (FMM "
-                                  f"order {inner_order} inner / 40 FP64 residuals; near-field "
+                                  f"order {inner_order} inner / {resid_order} FP64 residuals; near-field "
                                   f"caches), one graph-replayed "
                                   f"iteration for the whole batch; the forces of every "
                                   f"configuration in one batched pass" if forest and thr == 0
@@ -625,13 +633,13 @@ def bench_batch(args):
                                   f"iteration for the whole batch: {int((~lane).sum())} below "
                                   f"{thr} nodes with the fused direct far field, {int(lane.sum())} "
                                   f"from {thr} nodes on as trees of the FMM forest (FMM order "
-                                  f"{inner_order} inner / 40 FP64 residuals); the forces of every "
+                                  f"{inner_order} inner / {resid_order} FP64 residuals); the forces of every "
                                   f"configuration in one batched pass" if forest
                                   else f"{int((~lane).sum())} configurations below {thr} nodes in the "
                                   f"fused direct engine (graph-replayed iteration), "
                                   f"{int(lane.sum())} from {thr} nodes on in the FMM lane "
-                                  f"({args.fmm_workers} workers, FMM order {inner_order} inner / 40 "
-                                  f"FP64 residuals)" if hybrid
+                                  f"({args.fmm_workers} workers, FMM order {inner_order} inner / "
+                                  f"{resid_order} FP64 residuals)" if hybrid
                                   else ("the configurations below %d nodes only, all in the fused "
                                         "direct engine" % min_nodes if engine_only
                                         else "every configuration in the fused direct engine")),
