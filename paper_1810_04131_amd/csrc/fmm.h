@@ -181,6 +181,8 @@ struct FmmForest {
   // work items (member, index within the member's launch of that pass)
   DevBuf<int2> it_gather, it_p2m, it_pack, it_m2l, it_leaf2, it_leaf4, it_leaves;
   DevBuf<int2> it_cleaf;         // leaves of the trees whose near-field cache the pass reads
+  DevBuf<int2> it_cp2m;          // leaves of the trees holding P2M coefficients
+  int n_cp2m = 0;
   int n_cleaf = 0, n_leaves = 0; // n_leaves: every leaf (it_leaves)
   std::vector<DevBuf<int2>> it_tree;   // per parent level l: M2M into / L2L out of level l
   int n_gather = 0, n_p2m = 0, n_pack = 0, n_m2l = 0, n_leaf2 = 0, n_leaf4 = 0;

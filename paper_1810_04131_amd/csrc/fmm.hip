@@ -366,6 +366,70 @@ __device__ __forceinline__ void p2m_cached_leaf(int b, int p, const int* __restr
   if (lane < R) as_gm(reinterpret_cast<double*>(M))[(int64_t)as_k(gid)[b] * R + lane] = (double)acc;
 }
 
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+typedef double dbl2v __attribute__((ext_vector_type(2)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// p2m_cached_leaf for one wavefront of a multi-wave block.  The leaf's coefficients
+// are one contiguous block of cnt R floats (R = 2 (p + 1)); lane l reads its float4
+// chunks l, l + 64, ..., so when R divides 256 (and 4 divides R) the lane's four
+// components m = 4 l mod R, ..., m + 3 stay fixed while its node advances by 256 / R
+// per load.  All of a leaf's loads are issued before their first use; lanes with the
+// same m (l mod R / 4) are summed by cross-lane exchanges.  Other orders take
+// p2m_cached_leaf's lane-per-component loop.
+__device__ __forceinline__ void p2m_cached_wave(int b, int p, const int* __restrict__ ls,
+                                                const int* __restrict__ lc,
+                                                const int* __restrict__ gid,
+                                                const float* __restrict__ coef,
+                                                const double* __restrict__ ssd,
+                                                double2* __restrict__ M) {
+  const int R = 2 * (p + 1);
+  if (R % 4 != 0 || 256 % R != 0) {
+    p2m_cached_leaf(b, p, ls, lc, gid, coef, ssd, M);
+    return;
+  }
+  constexpr int U = 8;
+  const int lane = threadIdx.x % FB;
+  const int s0 = as_k(ls)[b], cnt = as_k(lc)[b];
+  const int npl = 256 / R;                  // nodes per wave load
+  const int jl = (4 * lane) / R, m = (4 * lane) % R;
+  const int nld = (cnt + npl - 1) / npl;    // wave loads of the leaf
+  const gptr<f32x4> cb = as_g(reinterpret_cast<const f32x4*>(coef + (int64_t)s0 * R));
+  const gptr<double> sb = as_g(ssd + s0);
+  f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+  for (int k0 = 0; k0 < nld; k0 += U) {
+    f32x4 c[U];
+    double sv[U];
+#pragma unroll
+    for (int v = 0; v < U; ++v) {
+      // past the leaf's last node: re-read that node (in bounds), weight zero below
+      const int j = min((k0 + v) * npl + jl, cnt - 1);
+      c[v] = cb[(j * R + m) >> 2];
+      sv[v] = sb[j];
+    }
+#pragma unroll
+    for (int v = 0; v < U; ++v) {
+      const float w = (k0 + v) * npl + jl < cnt ? (float)sv[v] : 0.0f;
+      acc.x = fmaf(c[v].x, w, acc.x);
+      acc.y = fmaf(c[v].y, w, acc.y);
+      acc.z = fmaf(c[v].z, w, acc.z);
+      acc.w = fmaf(c[v].w, w, acc.w);
+    }
+  }
+  for (int off = R / 4; off < FB; off *= 2) {
+    acc.x += __shfl_xor(acc.x, off);
+    acc.y += __shfl_xor(acc.y, off);
+    acc.z += __shfl_xor(acc.z, off);
+    acc.w += __shfl_xor(acc.w, off);
+  }
+  if (lane < R / 4) {
+    const gmut<dbl2v> o = as_gm(reinterpret_cast<dbl2v*>(reinterpret_cast<double*>(M) +
+                                                         (int64_t)as_k(gid)[b] * R + m));
+    o[0] = dbl2v{(double)acc.x, (double)acc.y};
+    o[1] = dbl2v{(double)acc.z, (double)acc.w};
+  }
+}
+
 __global__ __launch_bounds__(64) void p2m_kernel(int p, int use_col, double kappa,
                                                  const int* __restrict__ ls,
                                                  const int* __restrict__ lc,
@@ -437,8 +501,6 @@ __global__ void m2l_kernel(int p, int nbox, const int* __restrict__ ilp, const i
 // gathers the 16 source vectors (zero where a target has none there) and
 // accumulates A_o B with v_mfma_f64_16x16x4f64 (FP64, so the FMM keeps its
 // accuracy).  All levels go in one launch: their M2L terms are independent.
-typedef double dbl4 __attribute__((ext_vector_type(4)));
-typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 // Translation matrices in the operand order of the 16x16x4 product: lane =
 // i + 16 kk holds A[16 rt + i][4 ks + kk].  Row order (packed = 0, the M2M and
@@ -2040,6 +2102,10 @@ __global__ void forest_gather_kernel(const FmmDev* __restrict__ fd, const int2* 
   const int64_t k = (int64_t)it.y * 256 + threadIdx.x;
   if (k >= d.N) return;
   const double* sigma = V + (col ? (int64_t)col[d.cfg] * T : 0) + d.off;
+  if (d.pc32) {   // P2M and the leaf pass both read the cache: only the sorted densities
+    as_gm(d.ss)[k] = as_g(sigma)[as_g(d.perm)[k]];
+    return;
+  }
   gather_one(k, d.perm, sigma, d.wnxs, d.wnys, d.qx, d.qy, d.ss);
 }
 
@@ -2051,12 +2117,22 @@ __global__ __launch_bounds__(64) void forest_p2m_kernel(const FmmDev* __restrict
   const int2 it = items[blockIdx.x];
   const FmmDev& d = fd[it.x];
   if (!mask[d.cfg]) return;
-  if (d.pc32) {
-    p2m_cached_leaf(it.y, p, d.leaf_start, d.leaf_cnt, d.leaf_gid, d.pc32, d.ss, d.Mall);
-    return;
-  }
   p2m_leaf(it.y, p, use_col, d.kappa, d.leaf_start, d.leaf_cnt, d.leaf_gid, d.leaf_cx, d.leaf_cy,
            d.xs, d.ys, d.qx, d.qy, d.Mall, itab);
+}
+
+// P2M of the trees holding the P2M coefficients: items (member, leaf), CW per block.
+__global__ __launch_bounds__(FB * CW) void forest_cp2m_kernel(const FmmDev* __restrict__ fd,
+                                                              const int2* __restrict__ items,
+                                                              int n, const int* __restrict__ mask,
+                                                              int p) {
+  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / FB));
+  const int i = blockIdx.x * CW + w;
+  if (i >= n) return;
+  const int2 it = items[i];
+  const FmmDev& d = fd[it.x];
+  if (!mask[d.cfg]) return;
+  p2m_cached_wave(it.y, p, d.leaf_start, d.leaf_cnt, d.leaf_gid, d.pc32, d.ss, d.Mall);
 }
 
 // M2M into parent level l (GATHER) or L2L out of it, for every member deep enough.
@@ -2207,13 +2283,13 @@ void FmmForest::build(const std::vector<Tree>& trees, bool p2p32, hipStream_t s)
   nmem = (int)trees.size();
   f32 = p2p32;
   depth = 0;
-  n_gather = n_p2m = n_pack = n_m2l = n_leaf2 = n_leaf4 = n_cleaf = n_leaves = 0;
+  n_gather = n_p2m = n_cp2m = n_pack = n_m2l = n_leaf2 = n_leaf4 = n_cleaf = n_leaves = 0;
   if (nmem == 0) return;
   p = trees[0].fmm->p;
   R16 = trees[0].fmm->R16;
   m2l32 = p2p32 && trees[0].fmm->want_m2l32;
   std::vector<FmmDev> h(nmem);
-  std::vector<int2> g, pm, pk, ml, l2, l4, cl, la;
+  std::vector<int2> g, pm, cp, pk, ml, l2, l4, cl, la;
   std::vector<std::vector<int2>> tr(DMAX + 1);
   for (int m = 0; m < nmem; ++m) {
     Fmm& f = *trees[m].fmm;
@@ -2275,7 +2351,7 @@ void FmmForest::build(const std::vector<Tree>& trees, bool p2p32, hipStream_t s)
     }
     depth = std::max(depth, f.depth);
     for (int64_t b = 0; b < (f.N + 255) / 256; ++b) g.push_back(make_int2(m, (int)b));
-    for (int b = 0; b < f.nleaf; ++b) pm.push_back(make_int2(m, b));
+    for (int b = 0; b < f.nleaf; ++b) (d.pc32 ? cp : pm).push_back(make_int2(m, b));
     const int RT = R16 / 16;
     for (int l = 2; l < f.depth; ++l) {
       const int nb = f.lv[l].nbox;
@@ -2296,6 +2372,8 @@ void FmmForest::build(const std::vector<Tree>& trees, bool p2p32, hipStream_t s)
   YQ_HIP(hipMemcpyAsync(dev.p, h.data(), nmem * sizeof(FmmDev), hipMemcpyHostToDevice, s));
   upload_items(it_gather, g, s);
   upload_items(it_p2m, pm, s);
+  upload_items(it_cp2m, cp, s);
+  n_cp2m = (int)cp.size();
   upload_items(it_pack, pk, s);
   upload_items(it_m2l, ml, s);
   upload_items(it_leaf2, l2, s);
@@ -2377,6 +2455,9 @@ void FmmForest::expansions(const int* mask, const double* V, const int* col, int
   if (n_p2m)
     forest_p2m_kernel<<<n_p2m, 64, use_col ? (size_t)(p + 2) * 64 * sizeof(double) : 0, s>>>(
         dev.p, it_p2m.p, mask, p, use_col);
+  if (n_cp2m)
+    forest_cp2m_kernel<<<(n_cp2m + CW - 1) / CW, FB * CW, 0, s>>>(dev.p, it_cp2m.p, n_cp2m, mask,
+                                                                  p);
   YQ_HIP(hipGetLastError());
 #define YQ_FTREE(rt, G) \
   forest_tree_kernel<rt, G><<<n_tree[l], 256, 0, s>>>(dev.p, it_tree[l].p, mask, p, l)
