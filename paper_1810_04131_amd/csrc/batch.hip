@@ -585,8 +585,51 @@ __device__ __forceinline__ double bsum(double v, double* sh) {
   return r;
 }
 
+// The batched Krylov kernels below run over the kblk items (c, lb): KR rows of
+// configuration c from row lb KR on, KB2 threads, KU rows per thread; a block whose
+// configuration is masked off returns after one load.
+constexpr int KU = KR / KB2;
+
+// One multi-dot pass over NV columns of A: acc[v] = sum over the thread's rows of
+// A[(k0 + v) lda + i] w_i, summed over the block into partial[kpoff + k kb + lb].
+// sh: [KB2 / 64][8] doubles (the caller alternates two so that one barrier per pass
+// separates a pass's reads from the next-but-one pass's writes).
+template <int NV>
+__device__ __forceinline__ void mdot_pass(const double* __restrict__ ap, int64_t lda, int nr,
+                                          const double (&wr)[KU], double (*sh)[8],
+                                          double* __restrict__ out, int64_t ostride) {
+  double acc[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+#pragma unroll 4
+  for (int u = 0; u < KU; ++u) {
+    const int i = threadIdx.x + u * KB2;
+    const int ic = i < nr ? i : 0;   // a row of the block; its w is zero past nr
+    double a[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) a[v] = ap[(int64_t)v * lda + ic];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc[v] = fma(a[v], wr[u], acc[v]);
+  }
+#pragma unroll
+  for (int v = 0; v < NV; ++v)
+    for (int o = 32; o > 0; o >>= 1) acc[v] += __shfl_xor(acc[v], o);
+  const int wv = threadIdx.x / 64;
+  if (threadIdx.x % 64 == 0) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) sh[wv][v] = acc[v];
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < NV) {
+    double s = 0.0;
+    for (int q = 0; q < KB2 / 64; ++q) s += sh[q][threadIdx.x];
+    out[(int64_t)threadIdx.x * ostride] = s;
+  }
+}
+
 // partial[kpoff + k*kb + lb] = sum_{rows of block lb} A[k*lda + off + i] * w[off + i],
-// k < (jc ? jc[c] + 1 : 1).
+// k < (jc ? jc[c] + 1 : 1).  The block's w rows stay in registers; the columns go in
+// passes of 8 (then 4, 2, 1 for the rest), each a single block reduction.
 __global__ __launch_bounds__(KB2) void bmultidot_kernel(const ConfDev* __restrict__ cf,
                                                         const int2* __restrict__ blk,
                                                         const double* __restrict__ A, int64_t lda,
@@ -594,22 +637,37 @@ __global__ __launch_bounds__(KB2) void bmultidot_kernel(const ConfDev* __restric
                                                         const double* __restrict__ w,
                                                         const int* __restrict__ mask,
                                                         double* __restrict__ partial) {
-  __shared__ double sh[KB2];
+  __shared__ double sh[2][KB2 / 64][8];
   const int2 b = blk[blockIdx.x];
   const int c = b.x;
   if (!mask[c]) return;
   const ConfDev& cd = cf[c];
   const int kc = jc ? jc[c] + 1 : 1;
   const int64_t r0 = (int64_t)b.y * KR;
-  const int64_t r1 = min(cd.N, r0 + KR);
-  const double* wv = w + cd.off;
-  for (int k = 0; k < kc; ++k) {
-    const double* a = A + (int64_t)k * lda + cd.off;
-    double acc = 0.0;
-    for (int64_t i = r0 + threadIdx.x; i < r1; i += KB2) acc = fma(a[i], wv[i], acc);
-    const double s = bsum(acc, sh);
-    if (threadIdx.x == 0) partial[cd.kpoff + (int64_t)k * cd.kb + b.y] = s;
+  const int nr = (int)min((int64_t)KR, cd.N - r0);
+  const double* wp = w + cd.off + r0;
+  double wr[KU];
+#pragma unroll
+  for (int u = 0; u < KU; ++u) {
+    const int i = threadIdx.x + u * KB2;
+    wr[u] = i < nr ? wp[i] : 0.0;
   }
+  const double* ap = A + cd.off + r0;
+  double* out = partial + cd.kpoff + b.y;
+  int k0 = 0, par = 0;
+  for (; k0 + 8 <= kc; k0 += 8, par ^= 1)
+    mdot_pass<8>(ap + k0 * lda, lda, nr, wr, sh[par], out + (int64_t)k0 * cd.kb, cd.kb);
+  if (kc - k0 >= 4) {
+    mdot_pass<4>(ap + k0 * lda, lda, nr, wr, sh[par], out + (int64_t)k0 * cd.kb, cd.kb);
+    k0 += 4;
+    par ^= 1;
+  }
+  if (kc - k0 >= 2) {
+    mdot_pass<2>(ap + k0 * lda, lda, nr, wr, sh[par], out + (int64_t)k0 * cd.kb, cd.kb);
+    k0 += 2;
+    par ^= 1;
+  }
+  if (kc - k0 >= 1) mdot_pass<1>(ap + k0 * lda, lda, nr, wr, sh[par], out + (int64_t)k0 * cd.kb, cd.kb);
 }
 
 // out[c*stride + off + k] = sum_lb partial[kpoff + k*kb + lb]
@@ -628,22 +686,59 @@ __global__ void breduce_kernel(const ConfDev* __restrict__ cf, int nconf, int km
   out[(int64_t)c * stride + off + k] = s;
 }
 
-// w[g] += alpha * sum_{k < ncols(c)} V[k*T + g] * h[c*stride + off + k];
-// ncols = jc[c] + 1 (Arnoldi) or kc[c] (solution update).
-__global__ void bupdate_kernel(const int* __restrict__ node_conf, int64_t T,
-                               const int* __restrict__ mask, const int* __restrict__ jc,
-                               const int* __restrict__ kc, const double* __restrict__ V,
-                               const double* __restrict__ h, int stride, int off, double alpha,
-                               double* __restrict__ w) {
-  const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (g >= T) return;
-  const int c = node_conf[g];
-  if (c < 0 || !mask[c]) return;
+// w[g] += alpha * sum_{k < ncols(c)} V[k*T + g] * h[c*stride + off + k] on the block's
+// rows, ncols = jc[c] + 1 (Arnoldi) or kc[c] (solution update).  A thread keeps the sums
+// of its KU rows and loads two columns of all of them at once; each row's sum runs in k
+// order.
+__global__ __launch_bounds__(KB2) void bupdate_kernel(const ConfDev* __restrict__ cf,
+                                                      const int2* __restrict__ blk, int64_t T,
+                                                      const int* __restrict__ mask,
+                                                      const int* __restrict__ jc,
+                                                      const int* __restrict__ kc,
+                                                      const double* __restrict__ V,
+                                                      const double* __restrict__ h, int stride,
+                                                      int off, double alpha,
+                                                      double* __restrict__ w) {
+  const int2 b = blk[blockIdx.x];
+  const int c = b.x;
+  if (!mask[c]) return;
+  const ConfDev& cd = cf[c];
   const int n = jc ? jc[c] + 1 : kc[c];
+  const int64_t r0 = (int64_t)b.y * KR;
+  const int nr = (int)min((int64_t)KR, cd.N - r0);
   const double* hc = h + (int64_t)c * stride + off;
-  double s = 0.0;
-  for (int k = 0; k < n; ++k) s = fma(V[(int64_t)k * T + g], hc[k], s);
-  w[g] = fma(alpha, s, w[g]);
+  const double* vp = V + cd.off + r0;
+  double* wp = w + cd.off + r0;
+  int ir[KU];
+  double sum[KU];
+#pragma unroll
+  for (int u = 0; u < KU; ++u) {
+    const int i = threadIdx.x + u * KB2;
+    ir[u] = i < nr ? i : 0;   // past nr: a row of the block, its sum never stored
+    sum[u] = 0.0;
+  }
+  int k = 0;
+  for (; k + 2 <= n; k += 2) {
+    double a0[KU], a1[KU];
+#pragma unroll
+    for (int u = 0; u < KU; ++u) {
+      a0[u] = vp[(int64_t)k * T + ir[u]];
+      a1[u] = vp[(int64_t)(k + 1) * T + ir[u]];
+    }
+    const double h0 = hc[k], h1 = hc[k + 1];
+#pragma unroll
+    for (int u = 0; u < KU; ++u) sum[u] = fma(a1[u], h1, fma(a0[u], h0, sum[u]));
+  }
+  if (k < n) {
+    const double h0 = hc[k];
+#pragma unroll
+    for (int u = 0; u < KU; ++u) sum[u] = fma(vp[(int64_t)k * T + ir[u]], h0, sum[u]);
+  }
+#pragma unroll
+  for (int u = 0; u < KU; ++u) {
+    const int i = threadIdx.x + u * KB2;
+    if (i < nr) wp[i] = fma(alpha, sum[u], wp[i]);
+  }
 }
 
 // Device-side Arnoldi bookkeeping, one thread per configuration.
@@ -689,16 +784,24 @@ __global__ void bgivens_kernel(int nconf, int m, int* __restrict__ active, int* 
   }
 }
 
-// V[jc[c]*T + g] = w[g] * scale[c] for active configurations.
-__global__ void bscale_kernel(const int* __restrict__ node_conf, int64_t T,
-                              const int* __restrict__ mask, const int* __restrict__ jc,
-                              const double* __restrict__ scale, const double* __restrict__ w,
-                              double* __restrict__ V) {
-  const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (g >= T) return;
-  const int c = node_conf[g];
-  if (c < 0 || !mask[c]) return;
-  V[(int64_t)jc[c] * T + g] = w[g] * scale[c];
+// V[jc[c]*T + g] = w[g] * scale[c] on the block's rows.
+__global__ __launch_bounds__(KB2) void bscale_kernel(const ConfDev* __restrict__ cf,
+                                                     const int2* __restrict__ blk, int64_t T,
+                                                     const int* __restrict__ mask,
+                                                     const int* __restrict__ jc,
+                                                     const double* __restrict__ scale,
+                                                     const double* __restrict__ w,
+                                                     double* __restrict__ V) {
+  const int2 b = blk[blockIdx.x];
+  const int c = b.x;
+  if (!mask[c]) return;
+  const ConfDev& cd = cf[c];
+  const int64_t r0 = (int64_t)b.y * KR;
+  const int nr = (int)min((int64_t)KR, cd.N - r0);
+  const double sc = scale[c];
+  const double* wp = w + cd.off + r0;
+  double* vp = V + (int64_t)jc[c] * T + cd.off + r0;
+  for (int i = threadIdx.x; i < nr; i += KB2) vp[i] = wp[i] * sc;
 }
 
 // y = H^-1 g for the kc[c] columns of the finished cycle.
@@ -1062,13 +1165,14 @@ void Engine::iteration_part(int prec, int part) {
   const int nc = (int)members.size();
   const int hs = 2 * (m + 1) + 2;
   matvec_part(NPART - 1, prec, active.p, V.p, jc.p, w.p);
+  if (nkblk == 0) return;   // no configuration has nodes
   for (int pass = 0; pass < 2; ++pass) {
     bmultidot_kernel<<<nkblk, KB2, 0, stream>>>(conf.p, kblk.p, V.p, T, jc.p, w.p, active.p,
                                                 kpart.p);
     breduce_kernel<<<nb256((int64_t)nc * (m + 1)), 256, 0, stream>>>(
         conf.p, nc, m + 1, jc.p, active.p, kpart.p, hb.p, hs, pass * (m + 1));
-    bupdate_kernel<<<nb256(T), 256, 0, stream>>>(node_conf.p, T, active.p, jc.p, nullptr, V.p,
-                                                 hb.p, hs, pass * (m + 1), -1.0, w.p);
+    bupdate_kernel<<<nkblk, KB2, 0, stream>>>(conf.p, kblk.p, T, active.p, jc.p, nullptr, V.p,
+                                              hb.p, hs, pass * (m + 1), -1.0, w.p);
   }
   bmultidot_kernel<<<nkblk, KB2, 0, stream>>>(conf.p, kblk.p, w.p, 0, nullptr, w.p, active.p,
                                               kpart.p);
@@ -1077,7 +1181,7 @@ void Engine::iteration_part(int prec, int part) {
   bgivens_kernel<<<nb256(nc), 256, 0, stream>>>(nc, m, active.p, jc.p, kc.p, hb.p, hs, H.p, cs.p,
                                                 sn.p, gv.p, scale.p, bnorm.p, rtol.p, res.p,
                                                 conv.p);
-  bscale_kernel<<<nb256(T), 256, 0, stream>>>(node_conf.p, T, active.p, jc.p, scale.p, w.p, V.p);
+  bscale_kernel<<<nkblk, KB2, 0, stream>>>(conf.p, kblk.p, T, active.p, jc.p, scale.p, w.p, V.p);
   YQ_HIP(hipGetLastError());
 }
 
@@ -1209,8 +1313,9 @@ void Engine::read_profile(int prec, int kind, int64_t& launches, double& ms, dou
 void Engine::solve_cycle(const int* mask, double* x) {
   const int nc = (int)members.size();
   bsolve_kernel<<<nb256(nc), 256, 0, stream>>>(nc, m, mask, kc.p, H.p, gv.p, yv.p);
-  bupdate_kernel<<<nb256(T), 256, 0, stream>>>(node_conf.p, T, mask, nullptr, kc.p, V.p, yv.p, m,
-                                               0, 1.0, x);
+  if (nkblk)
+    bupdate_kernel<<<nkblk, KB2, 0, stream>>>(conf.p, kblk.p, T, mask, nullptr, kc.p, V.p, yv.p,
+                                              m, 0, 1.0, x);
   YQ_HIP(hipGetLastError());
 }
 
@@ -1307,7 +1412,7 @@ void Engine::gmres(int prec, const double* b, double* x, const std::vector<int>&
     YQ_HIP(hipMemcpyAsync(bnorm.p, bnv.data(), nc * sizeof(double), hipMemcpyHostToDevice, stream));
     YQ_HIP(hipMemcpyAsync(rtol.p, rt.data(), nc * sizeof(double), hipMemcpyHostToDevice, stream));
     // V0 = r / beta
-    bscale_kernel<<<nb256(T), 256, 0, stream>>>(node_conf.p, T, active.p, jc.p, scale.p, r.p, V.p);
+    bscale_kernel<<<nkblk, KB2, 0, stream>>>(conf.p, kblk.p, T, active.p, jc.p, scale.p, r.p, V.p);
     YQ_HIP(hipGetLastError());
     // iterate: at most m steps; the mask retires converged configurations
     int left = nact;
@@ -1319,7 +1424,7 @@ void Engine::gmres(int prec, const double* b, double* x, const std::vector<int>&
     // cycle end: y = H^-1 g and x += V y for the cycle's participants
     upload_mask(inc, act);
     bsolve_kernel<<<nb256(nc), 256, 0, stream>>>(nc, m, inc.p, kc.p, H.p, gv.p, yv.p);
-    bupdate_kernel<<<nb256(T), 256, 0, stream>>>(node_conf.p, T, inc.p, nullptr, kc.p, V.p, yv.p, m,
+    bupdate_kernel<<<nkblk, KB2, 0, stream>>>(conf.p, kblk.p, T, inc.p, nullptr, kc.p, V.p, yv.p, m,
                                                  0, 1.0, x);
     YQ_HIP(hipGetLastError());
     std::vector<int> hk(nc), hc(nc);

@@ -16,7 +16,9 @@ struct FmmLevel {
   DevBuf<int> cpos;               // position (0..3) in the parent
   DevBuf<int> ch;                 // children indices at level + 1 [4 * nbox], -1 if empty
   DevBuf<int> ilp, ils, ilo;      // interaction list: CSR over targets, source box, offset id
-  DevBuf<int> ild;                // the same as a dense table [nbox * 49] (-1: none)
+  DevBuf<int> ild;                // the same as a dense table [nbox * 49] (-1: none), its rows
+                                  // in the M2L order below
+  DevBuf<int> ord;                // M2L order: boxes sorted by the set of offsets holding a source
   double2* M = nullptr;           // expansions [nbox * (p + 1)], views into Fmm::Mall / Lall
   double2* L = nullptr;
 };
@@ -26,6 +28,7 @@ constexpr int DMAX = 14;   // deepest quadtree level
 // Per-level views of one tree for the M2L kernels.
 struct M2LLevels {
   const int* ild[DMAX + 1];
+  const int* ord[DMAX + 1];
   const double2* M[DMAX + 1];
   double2* L[DMAX + 1];
   int nbox[DMAX + 1];
@@ -76,7 +79,7 @@ struct Fmm {
   int R16 = 0;            // 2 (p + 1) rounded up to a multiple of 16
   DevBuf<double> amat;    // M2L matrices [level][offset][R16 * R16] in MFMA operand order
   DevBuf<double> gmat;    // M2M / L2L matrices [level][child position][R16 * R16], same order
-  DevBuf<int2> m2l_tiles; // (level, first box) of every 16-box M2L tile
+  DevBuf<int2> m2l_tiles; // (level, first position in the level's M2L order) of every 16-box M2L tile
   int n_m2l_tiles = 0;
   // FP32 M2L for the inner (FP32-class) applies: with s_n = n! (2 / (kappa w))^n per
   // level, the products run on M_n s_n and A_mn / (s_m s_n) in FP32 and give L_m / s_m

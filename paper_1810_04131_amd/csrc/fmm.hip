@@ -679,7 +679,8 @@ __global__ void m2l_pack_kernel(int p, int R, int64_t g0, int64_t g1, M2LLevels 
 // FP32 range, and L_m = (sum) s_m.  The four waves' tiles are summed in FP64 in a
 // fixed order.  Result layouts: FP64, lane l holds column l % 16, register j row
 // 4 j + l / 16; FP32, column l % 16, register j row 4 (l / 16) + j.
-// One tile tl = (level, first box); red: 3 RT 64 dbl4 of LDS.
+// One tile tl = (level, first position in the level's M2L order: the 16 boxes are
+// ord[tl.y ..], their list rows ild[tl.y ..]); red: 3 RT 64 dbl4 of LDS.
 template <typename T, int RT>
 __device__ __forceinline__ void m2l_tile(int2 tl, int p, const M2LLevels& lv,
                                          const T* __restrict__ amat, const T* __restrict__ Mp,
@@ -692,7 +693,8 @@ __device__ __forceinline__ void m2l_tile(int2 tl, int p, const M2LLevels& lv,
   const gptr<int> ild = as_g(lv.ild[l]);
   const int P1 = p + 1;
   const int col = lane & 15, kk = lane >> 4;
-  const int tb = tl.y + col;
+  const int q = tl.y + col;                                 // position in the M2L order
+  const int tb = q < nbox ? as_g(lv.ord[l])[q] : nbox;      // the box
   const gptr<T> Ml = as_g(Mp + lv.off[l] * R + kk * KS);
   const gptr<T> Al = as_g(amat + (int64_t)l * 49 * RT * 64 * KS + (int64_t)lane * KS);
   acc_t acc[RT];
@@ -700,7 +702,7 @@ __device__ __forceinline__ void m2l_tile(int2 tl, int p, const M2LLevels& lv,
   for (int rt = 0; rt < RT; ++rt) acc[rt] = acc_t{0, 0, 0, 0};
   for (int i = 0; i < NI; ++i) {
     const int o = far_offset(wave + 4 * i);
-    const int src = tb < nbox ? ild[(int64_t)tb * 49 + o] : -1;
+    const int src = q < nbox ? ild[(int64_t)q * 49 + o] : -1;
     if (__ballot(src >= 0) == 0) continue;    // no source at this offset in the tile
     T b[KS];
     const gptr<T> mb = Ml + (int64_t)(src >= 0 ? src : 0) * R;
@@ -1657,10 +1659,23 @@ void Fmm::build(int64_t n, double kap, int order, int lmax, const double* tab, h
       up(L.ilp, T.ilp);
       up(L.ils, T.ils);
       up(L.ilo, T.ilo);
-      std::vector<int> dense((size_t)L.nbox * 49, -1);
+      // M2L order: the boxes sorted by the set of offsets that hold a source, so that
+      // the 16 boxes of an M2L tile share most of their offsets (in Morton order the
+      // sparse boxes along curves share few, and a tile multiplies every offset any
+      // of its boxes uses)
+      std::vector<uint64_t> occ(L.nbox, 0);
       for (int b = 0; b < L.nbox; ++b)
-        for (int e = T.ilp[b]; e < T.ilp[b + 1]; ++e) dense[(size_t)b * 49 + T.ilo[e]] = T.ils[e];
+        for (int e = T.ilp[b]; e < T.ilp[b + 1]; ++e) occ[b] |= 1ull << T.ilo[e];
+      std::vector<int> ord(L.nbox);
+      for (int b = 0; b < L.nbox; ++b) ord[b] = b;
+      std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return occ[a] < occ[b]; });
+      std::vector<int> dense((size_t)L.nbox * 49, -1);
+      for (int q = 0; q < L.nbox; ++q) {
+        const int b = ord[q];
+        for (int e = T.ilp[b]; e < T.ilp[b + 1]; ++e) dense[(size_t)q * 49 + T.ilo[e]] = T.ils[e];
+      }
       up(L.ild, dense);
+      up(L.ord, ord);
       m2l_pairs += (int64_t)T.ils.size();
     }
   }
@@ -1807,6 +1822,7 @@ void Fmm::copy_tree(const Fmm& o, int q, const double* tab, hipStream_t s) {
       dup(lv[l].ils, o.lv[l].ils);
       dup(lv[l].ilo, o.lv[l].ilo);
       dup(lv[l].ild, o.lv[l].ild);
+      dup(lv[l].ord, o.lv[l].ord);
     }
   }
   dup(perm, o.perm);
@@ -1845,6 +1861,7 @@ M2LLevels Fmm::m2l_levels() const {
   M2LLevels a{};
   for (int l = 0; l <= depth; ++l) {
     a.ild[l] = l >= 2 ? lv[l].ild.p : nullptr;
+    a.ord[l] = l >= 2 ? lv[l].ord.p : nullptr;
     a.M[l] = lv[l].M;
     a.L[l] = lv[l].L;
     a.nbox[l] = lv[l].nbox;
