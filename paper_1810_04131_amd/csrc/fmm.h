@@ -18,7 +18,9 @@ struct FmmLevel {
   DevBuf<int> ilp, ils, ilo;      // interaction list: CSR over targets, source box, offset id
   DevBuf<int> ild;                // the same as a dense table [nbox * 49] (-1: none), its rows
                                   // in the M2L order below
-  DevBuf<int> ord;                // M2L order: boxes sorted by the set of offsets holding a source
+  DevBuf<int> ord;                // M2L order: boxes grouped by the sets of offsets holding a source
+  std::vector<uint64_t> occ;      // host: each box's set of far offsets holding a source (bit
+                                  // i: the i-th far offset), in the M2L order
   double2* M = nullptr;           // expansions [nbox * (p + 1)], views into Fmm::Mall / Lall
   double2* L = nullptr;
 };
@@ -79,7 +81,8 @@ struct Fmm {
   int R16 = 0;            // 2 (p + 1) rounded up to a multiple of 16
   DevBuf<double> amat;    // M2L matrices [level][offset][R16 * R16] in MFMA operand order
   DevBuf<double> gmat;    // M2M / L2L matrices [level][child position][R16 * R16], same order
-  DevBuf<int2> m2l_tiles; // (level, first position in the level's M2L order) of every 16-box M2L tile
+  DevBuf<int4> m2l_tiles; // every 16-box M2L tile: (level, first position in the level's M2L
+                          // order, the union of its boxes' offset sets as two 32-bit halves)
   int n_m2l_tiles = 0;
   // FP32 M2L for the inner (FP32-class) applies: with s_n = n! (2 / (kappa w))^n per
   // level, the products run on M_n s_n and A_mn / (s_m s_n) in FP32 and give L_m / s_m
@@ -164,7 +167,7 @@ struct FmmDev {
   const void* amat;        // M2L matrices (FP64, or the scaled FP32 copy)
   void* mpk;               // packed multipoles (FP64 or FP32)
   const double* msc;
-  const int2* m2l_tiles;
+  const int4* m2l_tiles;
   const double* tab;
   double* out;             // far field of the member's nodes, node order (2 pi / kappa^2 scaling)
   double* gout;            // its gradient [2 N] (x, then y), the gradient kernels' scaling

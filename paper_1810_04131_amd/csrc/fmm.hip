@@ -602,7 +602,7 @@ __device__ __forceinline__ dbl4 block_tile_sum(dbl4 acc, dbl4* red) {
 }
 
 // i-th of the 40 offsets (ox, oy) outside the 3 x 3 neighbourhood, as o = (ox+3) 7 + (oy+3).
-__device__ __forceinline__ int far_offset(int i) {
+__host__ __device__ __forceinline__ int far_offset(int i) {
   if (i < 14) return i;                                   // ox = -3, -2
   if (i < 26) {                                           // ox = -1, 0, 1: oy = -3, -2, 2, 3
     const int k = i - 14, c = k & 3;
@@ -670,25 +670,26 @@ __global__ void m2l_pack_kernel(int p, int R, int64_t g0, int64_t g1, M2LLevels 
 }
 
 // M2L on the matrix cores: L_m(t) = sum over the 40 far offsets o of A_o M(source at
-// o), for one 16-box tile of one level per block (4 waves; wave w takes offsets w,
-// w + 4, ...).  A wave loads each offset's 16 source vectors once (zero where a
-// target has no source there; offsets with no source in the tile are skipped) and
-// multiplies them with all RT row tiles of A_o.  T = double: FP64 products
+// o), for one 16-box tile of one level per block (4 waves; the offsets that hold a
+// source of some box of the tile, known from the tile, go to the waves in turn).  A
+// wave loads each of its offsets' 16 source vectors once (zero where a target has no
+// source there) and multiplies them with all RT row tiles of A_o.  T = double: FP64 products
 // (v_mfma_f64_16x16x4f64); T = float: FP32 products (v_mfma_f32_16x16x4f32) on the
 // scaled operands M_n s_n and A_mn / (s_m s_n), which keeps entries O(1) inside the
 // FP32 range, and L_m = (sum) s_m.  The four waves' tiles are summed in FP64 in a
 // fixed order.  Result layouts: FP64, lane l holds column l % 16, register j row
 // 4 j + l / 16; FP32, column l % 16, register j row 4 (l / 16) + j.
 // One tile tl = (level, first position in the level's M2L order: the 16 boxes are
-// ord[tl.y ..], their list rows ild[tl.y ..]); red: 3 RT 64 dbl4 of LDS.
+// ord[tl.y ..], their list rows ild[tl.y ..]; the union of their offset sets, bit i
+// the i-th far offset, low and high halves); red: 3 RT 64 dbl4 of LDS.
 template <typename T, int RT>
-__device__ __forceinline__ void m2l_tile(int2 tl, int p, const M2LLevels& lv,
+__device__ __forceinline__ void m2l_tile(int4 tl, int p, const M2LLevels& lv,
                                          const T* __restrict__ amat, const T* __restrict__ Mp,
                                          const double* __restrict__ msc, dbl4* red) {
-  constexpr int R = RT * 16, KS = R / 4, NI = 10;
+  constexpr int R = RT * 16, KS = R / 4;
   constexpr bool F32 = sizeof(T) == 4;
   using acc_t = typename std::conditional<F32, f32x4, dbl4>::type;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int l = tl.x, nbox = lv.nbox[l];
   const gptr<int> ild = as_g(lv.ild[l]);
   const int P1 = p + 1;
@@ -700,10 +701,14 @@ __device__ __forceinline__ void m2l_tile(int2 tl, int p, const M2LLevels& lv,
   acc_t acc[RT];
 #pragma unroll
   for (int rt = 0; rt < RT; ++rt) acc[rt] = acc_t{0, 0, 0, 0};
-  for (int i = 0; i < NI; ++i) {
-    const int o = far_offset(wave + 4 * i);
+  // the offsets used by the tile's boxes, dealt to the waves in turn
+  uint64_t um = ((uint64_t)(uint32_t)tl.w << 32) | (uint32_t)tl.z;
+  for (int r = 0; um != 0; ++r) {
+    const int i = __builtin_ctzll(um);
+    um &= um - 1;
+    if ((r & 3) != wave) continue;
+    const int o = far_offset(i);
     const int src = q < nbox ? ild[(int64_t)q * 49 + o] : -1;
-    if (__ballot(src >= 0) == 0) continue;    // no source at this offset in the tile
     T b[KS];
     const gptr<T> mb = Ml + (int64_t)(src >= 0 ? src : 0) * R;
 #pragma unroll
@@ -745,7 +750,7 @@ __device__ __forceinline__ void m2l_tile(int2 tl, int p, const M2LLevels& lv,
 }
 
 template <typename T, int RT>
-__global__ __launch_bounds__(256) void m2l_mfma_kernel(int p, const int2* __restrict__ tiles,
+__global__ __launch_bounds__(256) void m2l_mfma_kernel(int p, const int4* __restrict__ tiles,
                                                        M2LLevels lv, const T* __restrict__ amat,
                                                        const T* __restrict__ Mp,
                                                        const double* __restrict__ msc,
@@ -1590,6 +1595,48 @@ void Fmm::download(const double* dx, const double* dy, const double* dwnx, const
   N = n;
 }
 
+namespace {
+// M2L order of one level's boxes from their offset sets occ: a tile multiplies every
+// offset that any of its 16 boxes uses, and in Morton order the sparse boxes along
+// curves share few.  The boxes are sorted by their sets; each tile then starts at
+// the first unplaced box in that order and takes, one at a time, the unplaced box
+// among the next 32 that adds the fewest offsets to the tile's union.
+std::vector<int> m2l_order(const std::vector<uint64_t>& occ) {
+  const int nb = (int)occ.size();
+  std::vector<int> srt(nb);
+  std::iota(srt.begin(), srt.end(), 0);
+  std::stable_sort(srt.begin(), srt.end(), [&](int a, int b) { return occ[a] < occ[b]; });
+  std::vector<int> ord;
+  ord.reserve(nb);
+  std::vector<char> used(nb, 0);
+  constexpr int WIN = 32;
+  for (int s0 = 0; s0 < nb; ++s0) {
+    if (used[srt[s0]]) continue;
+    uint64_t u = occ[srt[s0]];
+    used[srt[s0]] = 1;
+    ord.push_back(srt[s0]);
+    for (int c = 1; c < 16; ++c) {
+      int best = -1, bgrow = 65;
+      for (int q = s0 + 1, seen = 0; q < nb && seen < WIN; ++q) {
+        if (used[srt[q]]) continue;
+        ++seen;
+        const int g = __builtin_popcountll(u | occ[srt[q]]) - __builtin_popcountll(u);
+        if (g < bgrow) {
+          bgrow = g;
+          best = srt[q];
+          if (g == 0) break;
+        }
+      }
+      if (best < 0) break;
+      used[best] = 1;
+      ord.push_back(best);
+      u |= occ[best];
+    }
+  }
+  return ord;
+}
+}  // namespace
+
 void Fmm::build(int64_t n, double kap, int order, int lmax, const double* tab, hipStream_t s) {
   YQ_REQUIRE(order >= 1 && order <= MAXP_FMM, YQ_EINVAL, "FMM order must be in 1..48");
   YQ_REQUIRE(lmax >= 1, YQ_EINVAL, "fmm_leaf_max must be >= 1");
@@ -1636,6 +1683,8 @@ void Fmm::build(int64_t n, double kap, int order, int lmax, const double* tab, h
   lv.resize(depth + 1);   // levels keep their device buffers from earlier builds
   nbox_total = 0;
   m2l_pairs = 0;
+  int far_index[49];   // offset (ox+3)*7+(oy+3) -> its rank among the 40 far offsets
+  for (int i = 0; i < 40; ++i) far_index[far_offset(i)] = i;
   for (int l = 0; l <= depth; ++l) {
     const qt::Level& T = t.lv[l];
     FmmLevel& L = lv[l];
@@ -1659,19 +1708,15 @@ void Fmm::build(int64_t n, double kap, int order, int lmax, const double* tab, h
       up(L.ilp, T.ilp);
       up(L.ils, T.ils);
       up(L.ilo, T.ilo);
-      // M2L order: the boxes sorted by the set of offsets that hold a source, so that
-      // the 16 boxes of an M2L tile share most of their offsets (in Morton order the
-      // sparse boxes along curves share few, and a tile multiplies every offset any
-      // of its boxes uses)
       std::vector<uint64_t> occ(L.nbox, 0);
       for (int b = 0; b < L.nbox; ++b)
-        for (int e = T.ilp[b]; e < T.ilp[b + 1]; ++e) occ[b] |= 1ull << T.ilo[e];
-      std::vector<int> ord(L.nbox);
-      for (int b = 0; b < L.nbox; ++b) ord[b] = b;
-      std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return occ[a] < occ[b]; });
+        for (int e = T.ilp[b]; e < T.ilp[b + 1]; ++e) occ[b] |= 1ull << far_index[T.ilo[e]];
+      const std::vector<int> ord = m2l_order(occ);
       std::vector<int> dense((size_t)L.nbox * 49, -1);
+      L.occ.resize(L.nbox);
       for (int q = 0; q < L.nbox; ++q) {
         const int b = ord[q];
+        L.occ[q] = occ[b];
         for (int e = T.ilp[b]; e < T.ilp[b + 1]; ++e) dense[(size_t)q * 49 + T.ilo[e]] = T.ils[e];
       }
       up(L.ild, dense);
@@ -1756,9 +1801,13 @@ void Fmm::set_order(int q, const double* tab, hipStream_t s) {
     YQ_HIP(hipGetLastError());
     // 16-box tiles of every level with M2L terms, finest level first
     Uploader up(s, stage_up, stage_dev);
-    std::vector<int2> ht;
+    std::vector<int4> ht;
     for (int l = depth; l >= 2; --l)
-      for (int b = 0; b < lv[l].nbox; b += 16) ht.push_back(make_int2(l, b));
+      for (int b = 0; b < lv[l].nbox; b += 16) {
+        uint64_t u = 0;
+        for (int q = b; q < std::min(b + 16, lv[l].nbox); ++q) u |= lv[l].occ[q];
+        ht.push_back(make_int4(l, b, (int)(uint32_t)u, (int)(uint32_t)(u >> 32)));
+      }
     up(m2l_tiles, ht);
     if (want_m2l32) {
       // s_n = n! (2 / (kappa w_l))^n, in logarithms (the factors themselves span
@@ -1823,6 +1872,7 @@ void Fmm::copy_tree(const Fmm& o, int q, const double* tab, hipStream_t s) {
       dup(lv[l].ilo, o.lv[l].ilo);
       dup(lv[l].ild, o.lv[l].ild);
       dup(lv[l].ord, o.lv[l].ord);
+      lv[l].occ = o.lv[l].occ;
     }
   }
   dup(perm, o.perm);
