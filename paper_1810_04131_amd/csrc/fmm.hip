@@ -591,16 +591,6 @@ __device__ __forceinline__ void tile_store(double2* __restrict__ y, int rt, int 
   }
 }
 
-// Sum of the four waves' tiles in a fixed order; the result is valid in wave 0.
-__device__ __forceinline__ dbl4 block_tile_sum(dbl4 acc, dbl4* red) {
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  if (wave > 0) red[(wave - 1) * 64 + lane] = acc;
-  __syncthreads();
-  if (wave == 0)
-    for (int w = 0; w < 3; ++w) acc += red[w * 64 + lane];
-  return acc;
-}
-
 // i-th of the 40 offsets (ox, oy) outside the 3 x 3 neighbourhood, as o = (ox+3) 7 + (oy+3).
 __host__ __device__ __forceinline__ int far_offset(int i) {
   if (i < 14) return i;                                   // ox = -3, -2
@@ -762,48 +752,66 @@ __global__ __launch_bounds__(256) void m2l_mfma_kernel(int p, const int4* __rest
 
 // M2M (GATHER: parent tiles at level l, y = sum over the 4 children of A_pos x_child)
 // and L2L (scatter: parent tiles, child_pos += A_pos x_parent), one level per
-// launch, one block (4 waves, wave = child position) per (16-box tile, row
-// tile); A points at the child level's 4 matrices, ch is the children table.
-// Block bx of the level's launch ((16-box tile, row tile) = (bx / RT, bx % RT)); red:
-// 3 x 64 dbl4 of LDS.
+// launch, one wavefront per item bx = (16-box tile, row tile) = (bx / RT, bx % RT):
+// the four child positions' products chain into one accumulator (M2M) or run as
+// four independent chains (L2L), with no exchange between wavefronts; A points at
+// the child level's 4 matrices, ch is the children table.
 template <int RT, bool GATHER>
 __device__ __forceinline__ void tree_tile(int bx, int p, int nbox, const int* __restrict__ ch,
                                           const double2* __restrict__ X,
                                           const double* __restrict__ amat,
-                                          double2* __restrict__ Y, dbl4* red) {
+                                          double2* __restrict__ Y) {
   constexpr int R = RT * 16, KS = R / 4;
-  const int lane = threadIdx.x & 63, pos = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
   const int rt = bx % RT;
   const int P1 = p + 1;
   const int col = lane & 15, kk = lane >> 4;
   const int tb = (bx / RT) * 16 + col;
-  const double* A = amat + (int64_t)pos * R * R + (int64_t)rt * KS * 64 + lane;
+  const double* A = amat + (int64_t)rt * KS * 64 + lane;
   const gptr<int> chg = as_g(ch);
-  const int c = tb < nbox ? chg[4 * (int64_t)tb + pos] : -1;
-  TileOps<KS> op;
+  int c[4];
+#pragma unroll
+  for (int pos = 0; pos < 4; ++pos) c[pos] = tb < nbox ? chg[4 * (int64_t)tb + pos] : -1;
   if (GATHER) {
-    tile_load<KS>(op, A, c >= 0 ? X + (int64_t)c * P1 : nullptr, P1, kk);
-    dbl4 acc = tile_mfma<KS>(op, dbl4{0.0, 0.0, 0.0, 0.0});
-    acc = block_tile_sum(acc, red);
+    dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int pos = 0; pos < 4; ++pos) {
+      TileOps<KS> op;
+      tile_load<KS>(op, A + (int64_t)pos * R * R, c[pos] >= 0 ? X + (int64_t)c[pos] * P1 : nullptr,
+                    P1, kk);
+      acc = tile_mfma<KS>(op, acc);
+    }
     // a leaf keeps the coefficients of its own nodes (P2M)
-    const bool split = tb < nbox && (chg[4 * (int64_t)tb] >= 0 || chg[4 * (int64_t)tb + 1] >= 0 ||
-                                     chg[4 * (int64_t)tb + 2] >= 0 || chg[4 * (int64_t)tb + 3] >= 0);
-    if (pos == 0 && split) tile_store<false>(Y + (int64_t)tb * P1, rt, kk, P1, acc);
+    if (c[0] >= 0 || c[1] >= 0 || c[2] >= 0 || c[3] >= 0)
+      tile_store<false>(Y + (int64_t)tb * P1, rt, kk, P1, acc);
   } else {
-    if (__ballot(c >= 0) == 0) return;          // whole wave: no child at this position
+    TileOps<KS> op;   // B: the parent's coefficients, shared by the four positions
     tile_load<KS>(op, A, tb < nbox ? X + (int64_t)tb * P1 : nullptr, P1, kk);
-    const dbl4 acc = tile_mfma<KS>(op, dbl4{0.0, 0.0, 0.0, 0.0});
-    if (c >= 0) tile_store<true>(Y + (int64_t)c * P1, rt, kk, P1, acc);
+    dbl4 acc[4];
+    acc[0] = tile_mfma<KS>(op, dbl4{0.0, 0.0, 0.0, 0.0});
+#pragma unroll
+    for (int pos = 1; pos < 4; ++pos) {
+      const gptr<double> Ag = as_g(A + (int64_t)pos * R * R);
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) op.a[ks] = Ag[ks * 64];
+      acc[pos] = tile_mfma<KS>(op, dbl4{0.0, 0.0, 0.0, 0.0});
+    }
+#pragma unroll
+    for (int pos = 0; pos < 4; ++pos)
+      if (c[pos] >= 0) tile_store<true>(Y + (int64_t)c[pos] * P1, rt, kk, P1, acc[pos]);
   }
 }
 
+// nitems (tile, row tile) items of one level, four per block.
 template <int RT, bool GATHER>
-__global__ __launch_bounds__(256) void tree_mfma_kernel(int p, int nbox, const int* __restrict__ ch,
+__global__ __launch_bounds__(256) void tree_mfma_kernel(int p, int nbox, int nitems,
+                                                        const int* __restrict__ ch,
                                                         const double2* __restrict__ X,
                                                         const double* __restrict__ amat,
                                                         double2* __restrict__ Y) {
-  __shared__ dbl4 red[3 * 64];
-  tree_tile<RT, GATHER>(blockIdx.x, p, nbox, ch, X, amat, Y, red);
+  const int i = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  if (i >= nitems) return;
+  tree_tile<RT, GATHER>(i, p, nbox, ch, X, amat, Y);
 }
 
 // L2L: child level lc from parents (table level lc), accumulated.
@@ -1958,16 +1966,17 @@ void Fmm::tree_mfma(bool gather, int l, hipStream_t s) {
   const int nb = lv[l].nbox;
   if (nb == 0) return;
   const int RT = R16 / 16;
-  const unsigned g = (unsigned)(((nb + 15) / 16) * RT);   // one block per (tile, row tile)
+  const int ni = ((nb + 15) / 16) * RT;   // one wave per (tile, row tile)
+  const unsigned g = (unsigned)((ni + 3) / 4);
   const double* A = gmat.p + (size_t)(l + 1) * 4 * R16 * R16;
   const double2* X = gather ? lv[l + 1].M : lv[l].L;
   double2* Y = gather ? lv[l].M : lv[l + 1].L;
   const int* ch = lv[l].ch.p;
 #define YQ_TREE(rt)                                                                  \
   if (gather)                                                                        \
-    tree_mfma_kernel<rt, true><<<g, 256, 0, s>>>(p, nb, ch, X, A, Y);                 \
+    tree_mfma_kernel<rt, true><<<g, 256, 0, s>>>(p, nb, ni, ch, X, A, Y);             \
   else                                                                               \
-    tree_mfma_kernel<rt, false><<<g, 256, 0, s>>>(p, nb, ch, X, A, Y);
+    tree_mfma_kernel<rt, false><<<g, 256, 0, s>>>(p, nb, ni, ch, X, A, Y);
   switch (RT) {
     case 1: YQ_TREE(1) break;
     case 2: YQ_TREE(2) break;
@@ -2205,18 +2214,19 @@ __global__ __launch_bounds__(FB * CW) void forest_cp2m_kernel(const FmmDev* __re
 // M2M into parent level l (GATHER) or L2L out of it, for every member deep enough.
 template <int RT, bool GATHER>
 __global__ __launch_bounds__(256) void forest_tree_kernel(const FmmDev* __restrict__ fd,
-                                                          const int2* __restrict__ items,
+                                                          const int2* __restrict__ items, int n,
                                                           const int* __restrict__ mask, int p,
                                                           int l) {
-  __shared__ dbl4 red[3 * 64];
-  const int2 it = items[blockIdx.x];
+  const int i = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  if (i >= n) return;
+  const int2 it = items[i];
   const FmmDev& d = fd[it.x];
   if (!mask[d.cfg]) return;
   constexpr int R = RT * 16;
   const double* A = d.gmat + (size_t)(l + 1) * 4 * R * R;
   const double2* X = GATHER ? d.lv.M[l + 1] : d.lv.L[l];
   double2* Y = GATHER ? const_cast<double2*>(d.lv.M[l]) : d.lv.L[l + 1];
-  tree_tile<RT, GATHER>(it.y, p, d.lv.nbox[l], d.ch[l], X, A, Y, red);
+  tree_tile<RT, GATHER>(it.y, p, d.lv.nbox[l], d.ch[l], X, A, Y);
 }
 
 template <typename T>
@@ -2527,7 +2537,8 @@ void FmmForest::expansions(const int* mask, const double* V, const int* col, int
                                                                   p);
   YQ_HIP(hipGetLastError());
 #define YQ_FTREE(rt, G) \
-  forest_tree_kernel<rt, G><<<n_tree[l], 256, 0, s>>>(dev.p, it_tree[l].p, mask, p, l)
+  forest_tree_kernel<rt, G><<<(n_tree[l] + 3) / 4, 256, 0, s>>>(dev.p, it_tree[l].p, n_tree[l], \
+                                                                mask, p, l)
 #define YQ_FTREE_ALL(G)                 \
   switch (RT) {                         \
     case 1: YQ_FTREE(1, G); break;      \
