@@ -15,6 +15,7 @@ struct FmmLevel {
   DevBuf<int> parent;             // index at level - 1
   DevBuf<int> cpos;               // position (0..3) in the parent
   DevBuf<int> ch;                 // children indices at level + 1 [4 * nbox], -1 if empty
+  DevBuf<int> tord;               // M2M / L2L order: boxes sorted by which children they have
   DevBuf<int> ilp, ils, ilo;      // interaction list: CSR over targets, source box, offset id
   DevBuf<int> ild;                // the same as a dense table [nbox * 49] (-1: none), its rows
                                   // in the M2L order below
@@ -163,6 +164,7 @@ struct FmmDev {
   double2 *Mall, *Lall;
   M2LLevels lv;
   const int* ch[DMAX + 1];
+  const int* tord[DMAX + 1];
   const double* gmat;      // M2M / L2L matrices
   const void* amat;        // M2L matrices (FP64, or the scaled FP32 copy)
   void* mpk;               // packed multipoles (FP64 or FP32)

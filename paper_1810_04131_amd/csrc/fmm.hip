@@ -752,12 +752,14 @@ __global__ __launch_bounds__(256) void m2l_mfma_kernel(int p, const int4* __rest
 
 // M2M (GATHER: parent tiles at level l, y = sum over the 4 children of A_pos x_child)
 // and L2L (scatter: parent tiles, child_pos += A_pos x_parent), one level per
-// launch, one wavefront per item bx = (16-box tile, row tile) = (bx / RT, bx % RT):
-// the four child positions' products chain into one accumulator (M2M) or run as
-// four independent chains (L2L), with no exchange between wavefronts; A points at
-// the child level's 4 matrices, ch is the children table.
+// launch, one wavefront per item bx = (16-box tile, row tile) = (bx / RT, bx % RT) of
+// the level's boxes in the order ord (sorted by which children they have): the child
+// positions' products chain into one accumulator (M2M) or run as independent chains
+// (L2L), a position that no box of the tile has skipped, with no exchange between
+// wavefronts; A points at the child level's 4 matrices, ch is the children table.
 template <int RT, bool GATHER>
 __device__ __forceinline__ void tree_tile(int bx, int p, int nbox, const int* __restrict__ ch,
+                                          const int* __restrict__ ord,
                                           const double2* __restrict__ X,
                                           const double* __restrict__ amat,
                                           double2* __restrict__ Y) {
@@ -766,7 +768,8 @@ __device__ __forceinline__ void tree_tile(int bx, int p, int nbox, const int* __
   const int rt = bx % RT;
   const int P1 = p + 1;
   const int col = lane & 15, kk = lane >> 4;
-  const int tb = (bx / RT) * 16 + col;
+  const int q = (bx / RT) * 16 + col;
+  const int tb = q < nbox ? as_g(ord)[q] : nbox;
   const double* A = amat + (int64_t)rt * KS * 64 + lane;
   const gptr<int> chg = as_g(ch);
   int c[4];
@@ -776,6 +779,7 @@ __device__ __forceinline__ void tree_tile(int bx, int p, int nbox, const int* __
     dbl4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int pos = 0; pos < 4; ++pos) {
+      if (__ballot(c[pos] >= 0) == 0) continue;
       TileOps<KS> op;
       tile_load<KS>(op, A + (int64_t)pos * R * R, c[pos] >= 0 ? X + (int64_t)c[pos] * P1 : nullptr,
                     P1, kk);
@@ -785,20 +789,21 @@ __device__ __forceinline__ void tree_tile(int bx, int p, int nbox, const int* __
     if (c[0] >= 0 || c[1] >= 0 || c[2] >= 0 || c[3] >= 0)
       tile_store<false>(Y + (int64_t)tb * P1, rt, kk, P1, acc);
   } else {
-    TileOps<KS> op;   // B: the parent's coefficients, shared by the four positions
-    tile_load<KS>(op, A, tb < nbox ? X + (int64_t)tb * P1 : nullptr, P1, kk);
-    dbl4 acc[4];
-    acc[0] = tile_mfma<KS>(op, dbl4{0.0, 0.0, 0.0, 0.0});
+    bool any[4];
 #pragma unroll
-    for (int pos = 1; pos < 4; ++pos) {
+    for (int pos = 0; pos < 4; ++pos) any[pos] = __ballot(c[pos] >= 0) != 0;
+    if (!(any[0] || any[1] || any[2] || any[3])) return;
+    TileOps<KS> op;   // B: the parent's coefficients, shared by the positions
+    tile_load<KS>(op, A, tb < nbox ? X + (int64_t)tb * P1 : nullptr, P1, kk);
+#pragma unroll
+    for (int pos = 0; pos < 4; ++pos) {
+      if (!any[pos]) continue;
       const gptr<double> Ag = as_g(A + (int64_t)pos * R * R);
 #pragma unroll
       for (int ks = 0; ks < KS; ++ks) op.a[ks] = Ag[ks * 64];
-      acc[pos] = tile_mfma<KS>(op, dbl4{0.0, 0.0, 0.0, 0.0});
+      const dbl4 acc = tile_mfma<KS>(op, dbl4{0.0, 0.0, 0.0, 0.0});
+      if (c[pos] >= 0) tile_store<true>(Y + (int64_t)c[pos] * P1, rt, kk, P1, acc);
     }
-#pragma unroll
-    for (int pos = 0; pos < 4; ++pos)
-      if (c[pos] >= 0) tile_store<true>(Y + (int64_t)c[pos] * P1, rt, kk, P1, acc[pos]);
   }
 }
 
@@ -806,12 +811,13 @@ __device__ __forceinline__ void tree_tile(int bx, int p, int nbox, const int* __
 template <int RT, bool GATHER>
 __global__ __launch_bounds__(256) void tree_mfma_kernel(int p, int nbox, int nitems,
                                                         const int* __restrict__ ch,
+                                                        const int* __restrict__ ord,
                                                         const double2* __restrict__ X,
                                                         const double* __restrict__ amat,
                                                         double2* __restrict__ Y) {
   const int i = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   if (i >= nitems) return;
-  tree_tile<RT, GATHER>(i, p, nbox, ch, X, amat, Y);
+  tree_tile<RT, GATHER>(i, p, nbox, ch, ord, X, amat, Y);
 }
 
 // L2L: child level lc from parents (table level lc), accumulated.
@@ -1712,6 +1718,20 @@ void Fmm::build(int64_t n, double kap, int order, int lmax, const double* tab, h
     up(L.parent, hpar);
     up(L.cpos, hpos);
     up(L.ch, T.child);
+    {
+      // M2M / L2L order: boxes sorted by the set of child positions they have, so
+      // that a 16-box tile skips the positions none of its boxes has (boxes along
+      // curves have about two children; leaves none)
+      std::vector<int> to(L.nbox);
+      std::iota(to.begin(), to.end(), 0);
+      auto pat = [&](int b) {
+        int m = 0;
+        for (int q = 0; q < 4; ++q) m |= (T.child[4 * (size_t)b + q] >= 0) << q;
+        return m;
+      };
+      std::stable_sort(to.begin(), to.end(), [&](int a, int b) { return pat(a) < pat(b); });
+      up(L.tord, to);
+    }
     if (l >= 2) {
       up(L.ilp, T.ilp);
       up(L.ils, T.ils);
@@ -1874,6 +1894,7 @@ void Fmm::copy_tree(const Fmm& o, int q, const double* tab, hipStream_t s) {
     dup(lv[l].parent, o.lv[l].parent);
     dup(lv[l].cpos, o.lv[l].cpos);
     dup(lv[l].ch, o.lv[l].ch);
+    dup(lv[l].tord, o.lv[l].tord);
     if (l >= 2) {
       dup(lv[l].ilp, o.lv[l].ilp);
       dup(lv[l].ils, o.lv[l].ils);
@@ -1972,11 +1993,12 @@ void Fmm::tree_mfma(bool gather, int l, hipStream_t s) {
   const double2* X = gather ? lv[l + 1].M : lv[l].L;
   double2* Y = gather ? lv[l].M : lv[l + 1].L;
   const int* ch = lv[l].ch.p;
+  const int* od = lv[l].tord.p;
 #define YQ_TREE(rt)                                                                  \
   if (gather)                                                                        \
-    tree_mfma_kernel<rt, true><<<g, 256, 0, s>>>(p, nb, ni, ch, X, A, Y);             \
+    tree_mfma_kernel<rt, true><<<g, 256, 0, s>>>(p, nb, ni, ch, od, X, A, Y);         \
   else                                                                               \
-    tree_mfma_kernel<rt, false><<<g, 256, 0, s>>>(p, nb, ni, ch, X, A, Y);
+    tree_mfma_kernel<rt, false><<<g, 256, 0, s>>>(p, nb, ni, ch, od, X, A, Y);
   switch (RT) {
     case 1: YQ_TREE(1) break;
     case 2: YQ_TREE(2) break;
@@ -2226,7 +2248,7 @@ __global__ __launch_bounds__(256) void forest_tree_kernel(const FmmDev* __restri
   const double* A = d.gmat + (size_t)(l + 1) * 4 * R * R;
   const double2* X = GATHER ? d.lv.M[l + 1] : d.lv.L[l];
   double2* Y = GATHER ? const_cast<double2*>(d.lv.M[l]) : d.lv.L[l + 1];
-  tree_tile<RT, GATHER>(it.y, p, d.lv.nbox[l], d.ch[l], X, A, Y);
+  tree_tile<RT, GATHER>(it.y, p, d.lv.nbox[l], d.ch[l], d.tord[l], X, A, Y);
 }
 
 template <typename T>
@@ -2410,7 +2432,10 @@ void FmmForest::build(const std::vector<Tree>& trees, bool p2p32, hipStream_t s)
     d.Mall = f.Mall.p;
     d.Lall = f.Lall.p;
     d.lv = f.m2l_levels();
-    for (int l = 0; l <= f.depth; ++l) d.ch[l] = f.lv[l].ch.p;
+    for (int l = 0; l <= f.depth; ++l) {
+      d.ch[l] = f.lv[l].ch.p;
+      d.tord[l] = f.lv[l].tord.p;
+    }
     d.gmat = f.gmat.p;
     d.msc = f.msc.p;
     d.m2l_tiles = f.m2l_tiles.p;
