@@ -116,15 +116,21 @@ __device__ inline void iscaled_col(double t, int nmax, double* col) {
   }
 }
 
-// It_n(x) = I_n(x) n! / (x/2)^n by its ascending series in t = x^2/4.
-__device__ __forceinline__ double iscaled_series(double t, int n) {
-  double term = 1.0, sum = 1.0;
+// It_n(x) = I_n(x) n! / (x/2)^n by its ascending series in t = x^2/4, for n = p
+// and p + 1 together: term k of It_n's series is t^k / (k! (n+1)...(n+k)),
+// both summed in one loop to a relative 1e-17.
+__device__ __forceinline__ void iscaled_pair(double t, int p, double& ip, double& ip1) {
+  double a = 1.0, b = 1.0, sa = 1.0, sb = 1.0;
   for (int k = 1; k < 200; ++k) {
-    term *= t * (recip(k) * recip(n + k));
-    sum += term;
-    if (term <= 1e-17 * sum) break;
+    const double tk = t * recip(k);
+    a *= tk * recip(p + k);
+    b *= tk * recip(p + 1 + k);
+    sa += a;
+    sb += b;
+    if (a <= 1e-17 * sa && b <= 1e-17 * sb) break;
   }
-  return sum;
+  ip = sa;
+  ip1 = sb;
 }
 
 // The local expansion L_0..L_p of a box with centre (cx, cy) at (xi, yi):
@@ -132,15 +138,16 @@ __device__ __forceinline__ double iscaled_series(double t, int n) {
 // as 2 Re S - L_0 It_0 with S = sum_n L_n It_n z^n / n!, z = (x/2) e^{i theta}: the
 // scaled It_n come down the recurrence of iscaled_col from the series of It_{p+1}
 // and It_p, and S is summed by Horner's rule in the same descending order
-// (registers only, no LDS column).
+// (registers only, no LDS column).  z = (kappa / 2)(dx + i dy) and t = |z|^2 need no
+// square root or division.
 __device__ __forceinline__ double l2p_value(double xi, double yi, double cx, double cy,
                                             double kappa, int p, const double2* __restrict__ lb) {
   const double dx = xi - cx, dy = yi - cy;
-  const double rho = sqrt(dx * dx + dy * dy);
-  const double x = kappa * rho, t = 0.25 * x * x, hx = 0.5 * x;
-  const double2 e1 = rho > 0.0 ? make_double2(dx / rho, dy / rho) : make_double2(1.0, 0.0);
-  const double2 z = make_double2(hx * e1.x, hx * e1.y);
-  double hi = iscaled_series(t, p + 1), cur = iscaled_series(t, p);
+  const double hk = 0.5 * kappa;
+  const double2 z = make_double2(hk * dx, hk * dy);
+  const double t = fma(z.x, z.x, z.y * z.y);
+  double cur, hi;
+  iscaled_pair(t, p, cur, hi);
   const gptr<double> lg = as_g(reinterpret_cast<const double*>(lb));   // (re, im) pairs
   double2 R = make_double2(lg[2 * p] * cur, lg[2 * p + 1] * cur);
   for (int n = p; n >= 1; --n) {
