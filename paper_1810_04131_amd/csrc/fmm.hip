@@ -343,6 +343,109 @@ __device__ __forceinline__ void p2m_leaf(int b, int p, int use_col, double kappa
   }
 }
 
+// One halving step of the exchange that sums 2 H values over the lanes: a lane keeps
+// the half of V[0, 2 H) that its lane bit H selects, sends the other half to the lane
+// that differs in that bit and adds what it receives, into V[0, H).
+template <int H>
+__device__ __forceinline__ void halve_sum(double* V, int lane) {
+  const bool up = (lane & H) != 0;
+#pragma unroll
+  for (int i = 0; i < H; ++i) {
+    const double keep = up ? V[H + i] : V[i];
+    const double send = up ? V[i] : V[H + i];
+    V[i] = keep + __shfl_xor(send, H, 64);
+  }
+}
+
+// p2m_leaf for an order P with 2 (P + 1) <= 64 without a wave sum per coefficient:
+// each lane adds the terms of its nodes for every n in registers (values
+// v = 2 n + (re, im), zero from 2 (P + 1) on), then six halving steps (H = 32 .. 1)
+// leave the sum of value l in lane l.  The terms use I_k(x) e^{i k phi} = It_k W_k with
+// W_k = z^k / k!, z = (kappa / 2)(dx + i dy), and It_k down the recurrence of
+// iscaled_col from the series of It_{P+1}, It_{P+2}: no square root or division.
+template <int P>
+__device__ __forceinline__ void p2m_leaf_halving(int b, double kappa, const int* __restrict__ ls,
+                                                 const int* __restrict__ lc,
+                                                 const int* __restrict__ gid,
+                                                 const double* __restrict__ ccx,
+                                                 const double* __restrict__ ccy,
+                                                 const double* __restrict__ xs,
+                                                 const double* __restrict__ ys,
+                                                 const double* __restrict__ qx,
+                                                 const double* __restrict__ qy,
+                                                 double2* __restrict__ M) {
+  static_assert(2 * (P + 1) <= 64, "one value per lane");
+  const int lane = threadIdx.x % FB;
+  const int s0 = as_k(ls)[b], cnt = as_k(lc)[b];
+  const double cx = as_k(ccx)[b], cy = as_k(ccy)[b];
+  const double hk = 0.5 * kappa;
+  double V[64];
+#pragma unroll
+  for (int v = 0; v < 64; ++v) V[v] = 0.0;
+  for (int r0 = 0; r0 < cnt; r0 += FB) {
+    const int j = r0 + lane;
+    double dx = 0.0, dy = 0.0;
+    double2 Q = make_double2(0.0, 0.0);
+    if (j < cnt) {
+      dx = as_g(xs)[s0 + j] - cx;
+      dy = as_g(ys)[s0 + j] - cy;
+      Q = make_double2(as_g(qx)[s0 + j], as_g(qy)[s0 + j]);
+    }
+    const double2 z = make_double2(hk * dx, hk * dy);
+    const double t = fma(z.x, z.x, z.y * z.y);
+    double It[P + 2], top;
+    iscaled_pair(t, P + 1, It[P + 1], top);
+    It[P] = fma(t * top, recip(P + 1) * recip(P + 2), It[P + 1]);
+#pragma unroll
+    for (int n = P; n >= 1; --n) It[n - 1] = fma(t * It[n + 1], recip(n) * recip(n + 1), It[n]);
+    const double2 Qc = cconj(Q);
+    double2 Wm = make_double2(0.0, 0.0), W0 = make_double2(1.0, 0.0), Wp = z;   // W_{n-1,n,n+1}
+#pragma unroll
+    for (int n = 0; n <= P; ++n) {
+      const double2 gp = make_double2(It[n + 1] * Wp.x, -It[n + 1] * Wp.y);   // conj(g_{n+1})
+      const double2 gm = n == 0 ? make_double2(It[1] * Wp.x, It[1] * Wp.y)   // g_1
+                                : make_double2(It[n - 1] * Wm.x, -It[n - 1] * Wm.y);
+      const double2 c = cmad(Q, gp, cmul(Qc, gm));
+      V[2 * n] += c.x;
+      V[2 * n + 1] += c.y;
+      Wm = W0;
+      W0 = Wp;
+      const double2 zw = cmul(Wp, z);
+      Wp = make_double2(zw.x * recip(n + 2), zw.y * recip(n + 2));
+    }
+  }
+  halve_sum<32>(V, lane);
+  halve_sum<16>(V, lane);
+  halve_sum<8>(V, lane);
+  halve_sum<4>(V, lane);
+  halve_sum<2>(V, lane);
+  halve_sum<1>(V, lane);
+  if (lane < 2 * (P + 1))
+    as_gm(reinterpret_cast<double*>(M))[(int64_t)as_k(gid)[b] * 2 * (P + 1) + lane] =
+        V[0] * (kappa / (4.0 * PI));
+}
+
+// p2m_leaf, by p2m_leaf_halving for the orders it is instantiated for.
+__device__ __forceinline__ void p2m_leaf_any(int b, int p, int use_col, double kappa,
+                                             const int* __restrict__ ls, const int* __restrict__ lc,
+                                             const int* __restrict__ gid,
+                                             const double* __restrict__ ccx,
+                                             const double* __restrict__ ccy,
+                                             const double* __restrict__ xs,
+                                             const double* __restrict__ ys,
+                                             const double* __restrict__ qx,
+                                             const double* __restrict__ qy,
+                                             double2* __restrict__ M, double* itab) {
+  if (p == 31)
+    p2m_leaf_halving<31>(b, kappa, ls, lc, gid, ccx, ccy, xs, ys, qx, qy, M);
+  else if (p == 20)
+    p2m_leaf_halving<20>(b, kappa, ls, lc, gid, ccx, ccy, xs, ys, qx, qy, M);
+  else if (p == 15)
+    p2m_leaf_halving<15>(b, kappa, ls, lc, gid, ccx, ccy, xs, ys, qx, qy, M);
+  else
+    p2m_leaf(b, p, use_col, kappa, ls, lc, gid, ccx, ccy, xs, ys, qx, qy, M, itab);
+}
+
 // M_n of leaf b from the P2M coefficients and the sorted densities: one wave, lane m
 // < 2 (p + 1) sums component m over the leaf's nodes in order (FP32 products and sums,
 // the inner operator's precision).
@@ -451,7 +554,7 @@ __global__ __launch_bounds__(64) void p2m_kernel(int p, int use_col, double kapp
                                                  const int* __restrict__ stop) {
   if (stop && *stop) return;   // a GMRES step queued after the stop
   extern __shared__ double itab[];
-  p2m_leaf(blockIdx.x, p, use_col, kappa, ls, lc, gid, ccx, ccy, xs, ys, qx, qy, M, itab);
+  p2m_leaf_any(blockIdx.x, p, use_col, kappa, ls, lc, gid, ccx, ccy, xs, ys, qx, qy, M, itab);
 }
 
 // M2M: parent level lp from children at level lp + 1 (table level lp + 1).
@@ -2222,8 +2325,8 @@ __global__ __launch_bounds__(64) void forest_p2m_kernel(const FmmDev* __restrict
   const int2 it = items[blockIdx.x];
   const FmmDev& d = fd[it.x];
   if (!mask[d.cfg]) return;
-  p2m_leaf(it.y, p, use_col, d.kappa, d.leaf_start, d.leaf_cnt, d.leaf_gid, d.leaf_cx, d.leaf_cy,
-           d.xs, d.ys, d.qx, d.qy, d.Mall, itab);
+  p2m_leaf_any(it.y, p, use_col, d.kappa, d.leaf_start, d.leaf_cnt, d.leaf_gid, d.leaf_cx,
+               d.leaf_cy, d.xs, d.ys, d.qx, d.qy, d.Mall, itab);
 }
 
 // P2M of the trees holding the P2M coefficients: items (member, leaf), CW per block.
