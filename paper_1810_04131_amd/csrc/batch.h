@@ -30,6 +30,9 @@ struct ConfDev {
   const int* xrow;
   const int* xpan;
   const double* xvals;
+  int qfold32, qfold64;   // the QBX correction is in the tree's FP32 / FP64 near-field cache
+  const uint32_t* qumask; // then: the panels left out of the fold (qf_umask, qf_xmask)
+  const uint8_t* qxmask;
   const double* tab;
   double* part64;
   float* part32;

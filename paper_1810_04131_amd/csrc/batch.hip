@@ -322,6 +322,35 @@ __global__ __launch_bounds__(BB) void bsym32_kernel(const ConfDev* __restrict__ 
 }
 
 // out[g] = (kappa^2/2pi) sum_chunks partial + correction, for every node of an active config.
+// correction_row over the panels that a QBX fold left out: window panel sl where bit
+// sl of um is set, extra-panel entry e where xm[e] is (bit 31: some entry is).
+template <typename TW>
+__device__ double correction_left(int64_t i, int64_t N, int P, int win, const TW* __restrict__ W,
+                                  const int* __restrict__ xrow, const int* __restrict__ xpan,
+                                  const double* __restrict__ xvals,
+                                  const double* __restrict__ sigma, uint32_t um,
+                                  const uint8_t* __restrict__ xm) {
+  const int64_t pan = i / Q, pid = pan / P;
+  const int k = (int)(pan % P);
+  double corr = 0.0;
+  for (int sl = 0; sl <= 2 * win; ++sl) {
+    if (!((um >> sl) & 1u)) continue;
+    int kj = (k + sl - win) % P;
+    if (kj < 0) kj += P;
+    const double* sg = sigma + (pid * P + kj) * Q;
+    const TW* wr = W + (int64_t)sl * Q * N + i;
+    for (int m = 0; m < Q; ++m) corr = fma((double)wr[(int64_t)m * N], sg[m], corr);
+  }
+  if (xvals && (um >> 31))
+    for (int e = xrow[i]; e < xrow[i + 1]; ++e) {
+      if (!xm[e]) continue;
+      const double* sg = sigma + (int64_t)xpan[e] * Q;
+      const double* vr = xvals + (int64_t)e * Q;
+      for (int m = 0; m < Q; ++m) corr = fma(vr[m], sg[m], corr);
+    }
+  return corr;
+}
+
 __global__ void bfinish_kernel(const ConfDev* __restrict__ cf, const int* __restrict__ node_conf,
                                int64_t T, const int* __restrict__ mask, int f32,
                                const double* __restrict__ V, const int* __restrict__ col,
@@ -341,11 +370,91 @@ __global__ void bfinish_kernel(const ConfDev* __restrict__ cf, const int* __rest
     for (int k = 0; k < cd.chunks32; ++k) s += (double)cd.part32[(int64_t)k * N + i];
   }
   s *= cd.kappa * cd.kappa / (2.0 * PI);
+  if (f32 ? cd.qfold32 : cd.qfold64) {   // the correction came with the tree's leaf pass
+    const uint32_t um = cd.qumask[i];      // but for the panels left out of the fold
+    out[g] = um == 0 ? s
+                     : s + (f32 && cd.W32 ? correction_left(i, N, cd.P, cd.win, cd.W32, cd.xrow,
+                                                            cd.xpan, cd.xvals, sg, um, cd.qxmask)
+                                          : correction_left(i, N, cd.P, cd.win, cd.W, cd.xrow,
+                                                            cd.xpan, cd.xvals, sg, um, cd.qxmask));
+    return;
+  }
   // the inner (FP32) operator reads the correction in FP32 when it is there
   const double corr =
       f32 && cd.W32 ? correction_row(i, N, cd.P, cd.win, cd.W32, cd.xrow, cd.xpan, cd.xvals, sg)
                     : correction_row(i, N, cd.P, cd.win, cd.W, cd.xrow, cd.xpan, cd.xvals, sg);
   out[g] = s + corr;
+}
+
+// ---- QBX corrections folded into the near-field caches -----------------------------------
+//
+// The QBX correction of target i, sum_j W_ij sigma_j over the nodes j of its window
+// panels and extra near panels (correction_row), involves sources that lie in the
+// P2P list of i's leaf, whose pairs the tree's near-field cache holds: the leaf pass
+// adds K_ij sigma_j in the far-field scaling (2 pi / kappa^2 times the operator's),
+// so adding W_ij 2 pi / kappa^2 to the cached K_ij gives the corrected sum in the same
+// pass, and the finish skips the correction's weights and densities.
+
+__global__ void iperm_kernel(int64_t n, const int* __restrict__ perm, int* __restrict__ iperm) {
+  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k < n) iperm[perm[k]] = k;
+}
+
+// Sorted target k (node i = perm[k]): each panel of correction_row's sums (the
+// 2 win + 1 window panels, then the extra panels of xrow) whose 16 nodes all lie in
+// the P2P list of k's leaf is folded: cache slot (entry e, source position, target
+// position, target-fastest) of each node j gets W_ij scale.  Panels with a node
+// outside the list are left out and recorded: bit sl of umask[i] for window panel
+// sl, xmask[e] = 1 (and bit 31) for extra-panel entry e.
+template <typename TC>
+__global__ void qbx_fold_kernel(int64_t N, int P, int win, const double* __restrict__ W,
+                                const int* __restrict__ xrow, const int* __restrict__ xpan,
+                                const double* __restrict__ xvals, const int* __restrict__ perm,
+                                const int* __restrict__ iperm, const int* __restrict__ leaf_of,
+                                const int* __restrict__ ls, const int* __restrict__ lc,
+                                const int* __restrict__ nbp, const int* __restrict__ nbi,
+                                const int64_t* __restrict__ boff, double scale, TC* coef,
+                                uint32_t* __restrict__ umask, uint8_t* __restrict__ xmask) {
+  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k >= N) return;
+  const int i = perm[k];
+  const int b = leaf_of[k];
+  const int t = (int)(k - ls[b]), cb = lc[b];
+  const int e0 = nbp[b], e1 = nbp[b + 1];
+  auto slot = [&](int64_t j) -> int64_t {
+    const int sj = iperm[j];
+    const int bj = leaf_of[sj];
+    for (int e = e0; e < e1; ++e)
+      if (nbi[e] == bj) return boff[e] + (int64_t)(sj - ls[bj]) * cb + t;
+    return -1;
+  };
+  // one panel: its 16 sources from j0, weights w[m * ws]
+  auto panel = [&](int64_t j0, const double* w, int64_t ws) -> bool {
+    int64_t a[Q];
+    bool ok = true;
+    for (int m = 0; m < Q; ++m) {
+      a[m] = slot(j0 + m);
+      ok = ok && a[m] >= 0;
+    }
+    if (ok)
+      for (int m = 0; m < Q; ++m) coef[a[m]] = (TC)((double)coef[a[m]] + w[m * ws] * scale);
+    return ok;
+  };
+  uint32_t um = 0;
+  const int64_t pan = i / Q, pid = pan / P;
+  const int kp = (int)(pan % P);
+  for (int sl = 0; sl <= 2 * win; ++sl) {
+    int kj = (kp + sl - win) % P;
+    if (kj < 0) kj += P;
+    if (!panel((pid * P + kj) * Q, W + (int64_t)sl * Q * N + i, N)) um |= 1u << sl;
+  }
+  if (xvals)
+    for (int e = xrow[i]; e < xrow[i + 1]; ++e) {
+      const bool ok = panel((int64_t)xpan[e] * Q, xvals + (int64_t)e * Q, 1);
+      xmask[e] = ok ? 0 : 1;
+      if (!ok) um |= 1u << 31;
+    }
+  umask[i] = um;
 }
 
 // ---- batched forces -----------------------------------------------------------------------
@@ -1019,6 +1128,52 @@ void Engine::rebuild() {
       }
     }
     near_bytes = used;
+  }
+  // QBX corrections folded into the caches just built (a kept cache keeps its fold);
+  // the panels left out are recorded with the configuration's geometry
+  {
+    DevBuf<int> ip;
+    bool used_ip = false;
+    for (int pass = 0; pass < 2; ++pass) {
+      const bool f64 = pass == 1;
+      for (auto& t : f64 ? thi : tin) {
+        Fmm& f = *t.fmm;
+        yq_problem* pb = members[t.cfg].pb;
+        if (f.nc_kind != (f64 ? 2 : 1) || !pb || !pb->W.n || f.N == 0) continue;
+        if (f.nc_folded && f.nc_folded != (const void*)pb->W.p)
+          f.build_near_cache(f64, t.tab, stream);   // folded from other weights
+        if (!f.nc_folded) {
+          const int64_t N = f.N;
+          if (ip.n < (size_t)N) {
+            if (used_ip) YQ_HIP(hipStreamSynchronize(stream));
+            ip.alloc((size_t)N);
+          }
+          used_ip = true;
+          pb->qf_umask.fit((size_t)N);
+          pb->qf_xmask.fit((size_t)std::max<int64_t>(pb->x_total, 1));
+          iperm_kernel<<<nb256(N), 256, 0, stream>>>(N, f.perm.p, ip.p);
+          const double scale = 2.0 * PI / (pb->kappa * pb->kappa);
+          const double* xv = pb->x_total > 0 ? pb->xvals.p : nullptr;
+#define YQ_FOLD(TC, C)                                                                             \
+  qbx_fold_kernel<TC><<<nb256(N), 256, 0, stream>>>(                                               \
+      N, pb->prm.panels_per_particle, pb->prm.qbx_window, pb->W.p, pb->xrow.p, pb->xpan.p, xv,     \
+      f.perm.p, ip.p, f.leaf_of.p, f.leaf_start.p, f.leaf_cnt.p, f.nbp.p, f.nbi.p, f.blk_off.p,     \
+      scale, C, pb->qf_umask.p, pb->qf_xmask.p)
+          if (f64)
+            YQ_FOLD(double, f.nc64.p);
+          else
+            YQ_FOLD(float, f.nc32.p);
+#undef YQ_FOLD
+          YQ_HIP(hipGetLastError());
+          f.nc_folded = pb->W.p;
+        }
+        ConfDev& d = h[t.cfg];
+        (f64 ? d.qfold64 : d.qfold32) = 1;
+        d.qumask = pb->qf_umask.p;
+        d.qxmask = pb->qf_xmask.p;
+      }
+    }
+    if (used_ip) YQ_HIP(hipStreamSynchronize(stream));   // before the scratch buffer goes
   }
   forest_in.build(tin, true, stream);
   forest_hi.build(thi, false, stream);

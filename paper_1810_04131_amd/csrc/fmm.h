@@ -70,6 +70,9 @@ struct Fmm {
   DevBuf<float> nc32;                 // FP32 coefficients (the inner operator's leaf pass)
   DevBuf<double> nc64;                // FP64 coefficients (the FP64 leaf pass)
   int nc_kind = 0;                    // 0 none, 1 FP32, 2 FP64
+  // the cache also holds the QBX corrections of these weights (set by whoever folds
+  // them in; cleared with the cache)
+  const void* nc_folded = nullptr;
   DevBuf<double> ss;                  // the density in sorted node order (cached passes)
   // P2M coefficients (with the FP32 cache): M_n of a leaf = sum over its sorted nodes
   // k of sigma_k pc32[k 2 (p + 1) + 2 n + (0: re, 1: im)]

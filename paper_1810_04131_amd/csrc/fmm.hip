@@ -2177,8 +2177,11 @@ void Fmm::apply(const double* sigma, double* partial, bool p2p_fp32, const doubl
                                                          Lall.p, partial, stop);
   const int nw = nleaf >= kLeavesFor2 ? 2 : PW;
   // the near-field cache of the apply's precision, if computed
-  const void* cache = p2p_fp32 ? (nc_kind == 1 ? (const void*)nc32.p : nullptr)
-                               : (nc_kind == 2 ? (const void*)nc64.p : nullptr);
+  // (a cache holding folded QBX corrections serves only the engine, whose finish
+  // leaves them out; here the caller's finish adds them)
+  const void* cache = nc_folded ? nullptr
+                      : p2p_fp32 ? (nc_kind == 1 ? (const void*)nc32.p : nullptr)
+                                 : (nc_kind == 2 ? (const void*)nc64.p : nullptr);
   if (cache) {
     auto k = p2p_fp32 ? p2p_cached_kernel<true> : p2p_cached_kernel<false>;
     k<<<(nleaf + CW - 1) / CW, FB * CW, 0, s>>>(nleaf, leaf_start.p, leaf_cnt.p, nbp.p, ent.p,
@@ -2261,6 +2264,7 @@ void Fmm::build_near_cache(bool f64, const double* tab, hipStream_t s) {
     out = nc32.p;
   }
   ss.fit(std::max<int64_t>(N, 1));
+  nc_folded = nullptr;
   auto k = f64 ? near_cache_kernel<true> : near_cache_kernel<false>;
   k<<<nleaf, 64, 0, s>>>(leaf_start.p, leaf_cnt.p, nbp.p, nbi.p, blk_off.p, xs.p, ys.p, wnxs.p,
                          wnys.p, kappa, tab, out);
@@ -2277,6 +2281,7 @@ void Fmm::build_near_cache(bool f64, const double* tab, hipStream_t s) {
 }
 
 void Fmm::drop_near_cache() {
+  nc_folded = nullptr;
   nc32.release();
   nc64.release();
   ss.release();

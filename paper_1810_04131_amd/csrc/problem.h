@@ -49,6 +49,11 @@ struct yq_problem {
   DevBuf<double> xvals, xgvals;
   DevBuf<double> W, WGx, WGy;
   DevBuf<float> W32;   // W rounded to FP32 (the batch engine's inner operator)
+  // QBX corrections folded into a near-field cache of this geometry: per node, bit sl
+  // set where window panel sl was left out of the fold (some node outside the leaf's
+  // P2P list), bit 31 where some extra panel was; per extra-panel entry, 1 where left out
+  DevBuf<uint32_t> qf_umask;
+  DevBuf<uint8_t> qf_xmask;
   const double* W32_src = nullptr;   // the W it was rounded from
   DevBuf<double> Lqbx, Lnear, Lpot, tab;
   Consts consts{};
