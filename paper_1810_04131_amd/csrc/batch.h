@@ -93,6 +93,8 @@ struct Engine {
   DevBuf<double> gx, gy, pen;   // forces: surface gradient [T], per-particle energies
   DevBuf<int2> fitems;          // forces: (configuration, particle) blocks
   int nfitems = 0;
+  DevBuf<int2> litems;          // (configuration, node) of the QBX corrections left out of folds
+  int nlitems = 0;
   // members with an FMM far field, as one forest per operator: the inner (FP32
   // leaf pairs and M2L) and the FP64 residual operator (the members' order-40 FMMs)
   FmmForest forest_in, forest_hi;

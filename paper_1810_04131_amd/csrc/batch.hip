@@ -371,12 +371,7 @@ __global__ void bfinish_kernel(const ConfDev* __restrict__ cf, const int* __rest
   }
   s *= cd.kappa * cd.kappa / (2.0 * PI);
   if (f32 ? cd.qfold32 : cd.qfold64) {   // the correction came with the tree's leaf pass
-    const uint32_t um = cd.qumask[i];      // but for the panels left out of the fold
-    out[g] = um == 0 ? s
-                     : s + (f32 && cd.W32 ? correction_left(i, N, cd.P, cd.win, cd.W32, cd.xrow,
-                                                            cd.xpan, cd.xvals, sg, um, cd.qxmask)
-                                          : correction_left(i, N, cd.P, cd.win, cd.W, cd.xrow,
-                                                            cd.xpan, cd.xvals, sg, um, cd.qxmask));
+    out[g] = s;                            // (bleft_kernel adds the panels left out)
     return;
   }
   // the inner (FP32) operator reads the correction in FP32 when it is there
@@ -384,6 +379,40 @@ __global__ void bfinish_kernel(const ConfDev* __restrict__ cf, const int* __rest
       f32 && cd.W32 ? correction_row(i, N, cd.P, cd.win, cd.W32, cd.xrow, cd.xpan, cd.xvals, sg)
                     : correction_row(i, N, cd.P, cd.win, cd.W, cd.xrow, cd.xpan, cd.xvals, sg);
   out[g] = s + corr;
+}
+
+// The corrections of the panels left out of the QBX folds, after bfinish_kernel: items
+// (configuration, node) of the nodes with such panels.
+__global__ void bleft_kernel(const ConfDev* __restrict__ cf, const int2* __restrict__ items, int n,
+                             int64_t T, const int* __restrict__ mask, int f32,
+                             const double* __restrict__ V, const int* __restrict__ col,
+                             double* __restrict__ out) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n) return;
+  const int2 it = items[q];
+  const int c = it.x;
+  if (!mask[c]) return;
+  const ConfDev& cd = cf[c];
+  if (!(f32 ? cd.qfold32 : cd.qfold64)) return;
+  const int64_t i = it.y;
+  const double* sg = V + (col ? (int64_t)col[c] * T : 0) + cd.off;
+  const uint32_t um = cd.qumask[i];
+  out[cd.off + i] += f32 && cd.W32 ? correction_left(i, cd.N, cd.P, cd.win, cd.W32, cd.xrow,
+                                                     cd.xpan, cd.xvals, sg, um, cd.qxmask)
+                                   : correction_left(i, cd.N, cd.P, cd.win, cd.W, cd.xrow,
+                                                     cd.xpan, cd.xvals, sg, um, cd.qxmask);
+}
+
+__global__ void qbx_left_kernel(int64_t N, const uint32_t* __restrict__ umask,
+                                int* __restrict__ left, int* __restrict__ cnt) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < N && umask[i]) left[atomicAdd(cnt, 1)] = (int)i;
+}
+
+__global__ void left_items_kernel(int64_t n, int c, const int* __restrict__ left,
+                                  int2* __restrict__ items) {
+  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k < n) items[k] = make_int2(c, left[k]);
 }
 
 // ---- QBX corrections folded into the near-field caches -----------------------------------
@@ -1134,6 +1163,7 @@ void Engine::rebuild() {
   {
     DevBuf<int> ip;
     bool used_ip = false;
+    std::vector<yq_problem*> refolded;
     for (int pass = 0; pass < 2; ++pass) {
       const bool f64 = pass == 1;
       for (auto& t : f64 ? thi : tin) {
@@ -1166,6 +1196,8 @@ void Engine::rebuild() {
 #undef YQ_FOLD
           YQ_HIP(hipGetLastError());
           f.nc_folded = pb->W.p;
+          if (std::find(refolded.begin(), refolded.end(), pb) == refolded.end())
+            refolded.push_back(pb);
         }
         ConfDev& d = h[t.cfg];
         (f64 ? d.qfold64 : d.qfold32) = 1;
@@ -1173,6 +1205,35 @@ void Engine::rebuild() {
         d.qxmask = pb->qf_xmask.p;
       }
     }
+    // the nodes with panels left out, per geometry folded now (kept folds keep theirs)
+    for (yq_problem* pb : refolded) {
+      pb->qf_left.fit((size_t)std::max<int64_t>(pb->N, 1));
+      pb->qf_cnt.fit(1);
+      fill_int_kernel<<<1, 256, 0, stream>>>(pb->qf_cnt.p, 1, 0);
+      qbx_left_kernel<<<nb256(pb->N), 256, 0, stream>>>(pb->N, pb->qf_umask.p, pb->qf_left.p,
+                                                        pb->qf_cnt.p);
+    }
+    std::vector<int> hc(refolded.size());
+    for (size_t q = 0; q < refolded.size(); ++q)
+      YQ_HIP(hipMemcpyAsync(&hc[q], refolded[q]->qf_cnt.p, sizeof(int), hipMemcpyDeviceToHost,
+                            stream));
+    YQ_HIP(hipStreamSynchronize(stream));
+    for (size_t q = 0; q < refolded.size(); ++q) refolded[q]->qf_nleft = hc[q];
+    // one list over the batch, in configuration order
+    int64_t nl = 0;
+    for (int c = 0; c < nc; ++c)
+      if ((h[c].qfold32 || h[c].qfold64) && members[c].pb) nl += members[c].pb->qf_nleft;
+    nlitems = (int)nl;
+    litems.fit((size_t)std::max<int64_t>(nl, 1));
+    nl = 0;
+    for (int c = 0; c < nc; ++c) {
+      yq_problem* pb = members[c].pb;
+      if (!(h[c].qfold32 || h[c].qfold64) || !pb || pb->qf_nleft == 0) continue;
+      left_items_kernel<<<nb256(pb->qf_nleft), 256, 0, stream>>>(pb->qf_nleft, c, pb->qf_left.p,
+                                                                  litems.p + nl);
+      nl += pb->qf_nleft;
+    }
+    YQ_HIP(hipGetLastError());
     if (used_ip) YQ_HIP(hipStreamSynchronize(stream));   // before the scratch buffer goes
   }
   forest_in.build(tin, true, stream);
@@ -1269,6 +1330,9 @@ void Engine::matvec_part(int part, int prec, const int* mask, const double* Vin,
   } else {
     bfinish_kernel<<<nb256(T), 256, 0, stream>>>(conf.p, node_conf.p, T, mask, prec == YQ_MIXED,
                                                  Vin, col, out);
+    if (nlitems)
+      bleft_kernel<<<nb256(nlitems), 256, 0, stream>>>(conf.p, litems.p, nlitems, T, mask,
+                                                       prec == YQ_MIXED, Vin, col, out);
   }
   YQ_HIP(hipGetLastError());
 }
@@ -1694,6 +1758,9 @@ void Engine::resid(const std::vector<int>& plain, const std::vector<int>& fused,
                                                       T, tab64.p);
   }
   bfinish_kernel<<<nb256(T), 256, 0, stream>>>(conf.p, node_conf.p, T, inc.p, 0, x, nullptr, out);
+  if (nlitems)
+    bleft_kernel<<<nb256(nlitems), 256, 0, stream>>>(conf.p, litems.p, nlitems, T, inc.p, 0, x,
+                                                     nullptr, out);
   YQ_HIP(hipGetLastError());
 }
 

@@ -54,6 +54,9 @@ struct yq_problem {
   // P2P list), bit 31 where some extra panel was; per extra-panel entry, 1 where left out
   DevBuf<uint32_t> qf_umask;
   DevBuf<uint8_t> qf_xmask;
+  DevBuf<int> qf_left;            // the nodes with a panel left out (qf_nleft of them)
+  DevBuf<int> qf_cnt;
+  int64_t qf_nleft = 0;
   const double* W32_src = nullptr;   // the W it was rounded from
   DevBuf<double> Lqbx, Lnear, Lpot, tab;
   Consts consts{};
