@@ -1147,7 +1147,7 @@ void Engine::rebuild() {
       for (auto& t : f64 ? thi : tin) {
         const int want = f64 ? 2 : 1;
         const int64_t need = t.fmm->near_cache_bytes(f64);
-        if (used + need <= budget) {
+        if (t.fmm->near_cacheable() && used + need <= budget) {
           if (t.fmm->nc_kind != want) t.fmm->build_near_cache(f64, t.tab, stream);
           used += need;
           (f64 ? near_trees64 : near_trees32) += 1;

@@ -136,6 +136,10 @@ struct Fmm {
   void build_near_cache(bool f64, const double* tab, hipStream_t s);
   void drop_near_cache();
   // device bytes build_near_cache(f64) takes
+  // The cached leaf pass hands a source leaf's densities to the lanes through one
+  // wavefront exchange, so it needs leaves of at most 64 nodes (a tree built with a
+  // larger leaf_max, or one whose depth limit left a bigger leaf, stays uncached).
+  bool near_cacheable() const { return built && max_leaf <= 64; }
   int64_t near_cache_bytes(bool f64) const {
     return p2p_pairs * (f64 ? 8 : 4) + N * 8 + (f64 ? 0 : N * 2 * (p + 1) * 4);
   }

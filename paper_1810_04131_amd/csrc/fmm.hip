@@ -2253,6 +2253,7 @@ __global__ __launch_bounds__(64) void p2m_coef_kernel(int p, int use_col, double
 
 void Fmm::build_near_cache(bool f64, const double* tab, hipStream_t s) {
   YQ_REQUIRE(nleaf > 0 && blk_off.p, YQ_ESTATE, "FMM tree not built");
+  YQ_REQUIRE(max_leaf <= 64, YQ_EINVAL, "near-field cache: leaves of more than 64 nodes");
   drop_near_cache();
   const size_t np = (size_t)std::max<int64_t>(p2p_pairs, 1);
   void* out;

@@ -509,6 +509,24 @@ def test_batch_leaf_pass_timers_count_pairs_and_leave_results_unchanged():
     assert n >= max(i["matvecs_fp32"] for i in infos) and 0 < pairs <= n * p1
 
 
+def test_batch_leaves_over_64_nodes_stay_uncached():
+    """The cached leaf pass hands a source leaf's densities to the lanes through one
+    wavefront exchange (at most 64 nodes): trees built with larger leaves keep the
+    passes that evaluate every pair, and their solves agree with the default trees'."""
+    _torch()
+    cfgs = _forest_configs()
+    prm = dict(panels_per_particle=P, qbx_order=ORDER, tol=1e-10, precision=1)
+    big = _lane_batch(cfgs, True, near=-1, fmm_leaf_max=200, **prm)
+    assert big.near_cache_info() == (0, 0, 0)
+    ref = _lane_batch(cfgs, True, near=-1, **prm)
+    for bt in (big, ref):
+        bt.set_boundary_data(bt.boundary_label())
+    sb, ib = big.solve()
+    sr, _ = ref.solve()
+    assert all(i["residual"] <= 1e-10 for i in ib)
+    assert _rel(_np(sb), _np(sr)) < 1e-8
+
+
 def test_batch_near_cache_matches_uncached_leaf_passes():
     """Forest trees with their near-field coefficients cached (FP32 inner, FP64
     residual operator) against the passes that evaluate every pair; the budget
