@@ -162,6 +162,9 @@ def parse():
                          "(default 31: its operator differs from the library's order 40 by "
                          "1e-13 relative, far below the 1e-9 tolerance, and 2 (p + 1) = 64 "
                          "fills the MFMA operand tiles; 0: the library's)")
+    ap.add_argument("--inner-tol", type=float, default=0.0,
+                    help="batch: relative tolerance of each FP32-operator inner solve (default 0: "
+                         "the library's, 1e-6)")
     ap.add_argument("--fmm-leaf", type=int, default=0,
                     help="batch: most nodes per FMM leaf (default 0: the library's, 64)")
     ap.add_argument("--near-cache-gb", type=float, default=None,
@@ -457,6 +460,8 @@ def bench_batch(args):
         prm.fmm_resid_order = args.fmm_resid_order
     if args.fmm_leaf:
         prm.fmm_leaf_max = args.fmm_leaf
+    if args.inner_tol:
+        prm.inner_tol = args.inner_tol
     inner_order = prm.fmm_order
     resid_order = prm.fmm_resid_order
     b = yq.Batch(prm)

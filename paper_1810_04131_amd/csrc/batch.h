@@ -90,6 +90,7 @@ struct Engine {
   DevBuf<int> active, inc, jc, kc, conv, pmask, fmask;
   DevBuf<double> hb, H, cs, sn, gv, yv, scale, bnorm, rtol, res, nrm;
   DevBuf<double> V, w, r, tmp, delta, f;
+  DevBuf<float> V32;             // the basis in FP32 (mixed solves' orthogonalisation)
   DevBuf<double> gx, gy, pen;   // forces: surface gradient [T], per-particle energies
   DevBuf<int2> fitems;          // forces: (configuration, particle) blocks
   int nfitems = 0;

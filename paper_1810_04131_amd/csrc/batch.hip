@@ -732,8 +732,8 @@ constexpr int KU = KR / KB2;
 // A[(k0 + v) lda + i] w_i, summed over the block into partial[kpoff + k kb + lb].
 // sh: [KB2 / 64][8] doubles (the caller alternates two so that one barrier per pass
 // separates a pass's reads from the next-but-one pass's writes).
-template <int NV>
-__device__ __forceinline__ void mdot_pass(const double* __restrict__ ap, int64_t lda, int nr,
+template <int NV, typename TA>
+__device__ __forceinline__ void mdot_pass(const TA* __restrict__ ap, int64_t lda, int nr,
                                           const double (&wr)[KU], double (*sh)[8],
                                           double* __restrict__ out, int64_t ostride) {
   double acc[NV];
@@ -745,7 +745,7 @@ __device__ __forceinline__ void mdot_pass(const double* __restrict__ ap, int64_t
     const int ic = i < nr ? i : 0;   // a row of the block; its w is zero past nr
     double a[NV];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) a[v] = ap[(int64_t)v * lda + ic];
+    for (int v = 0; v < NV; ++v) a[v] = (double)ap[(int64_t)v * lda + ic];
 #pragma unroll
     for (int v = 0; v < NV; ++v) acc[v] = fma(a[v], wr[u], acc[v]);
   }
@@ -768,9 +768,10 @@ __device__ __forceinline__ void mdot_pass(const double* __restrict__ ap, int64_t
 // partial[kpoff + k*kb + lb] = sum_{rows of block lb} A[k*lda + off + i] * w[off + i],
 // k < (jc ? jc[c] + 1 : 1).  The block's w rows stay in registers; the columns go in
 // passes of 8 (then 4, 2, 1 for the rest), each a single block reduction.
+template <typename TA>
 __global__ __launch_bounds__(KB2) void bmultidot_kernel(const ConfDev* __restrict__ cf,
                                                         const int2* __restrict__ blk,
-                                                        const double* __restrict__ A, int64_t lda,
+                                                        const TA* __restrict__ A, int64_t lda,
                                                         const int* __restrict__ jc,
                                                         const double* __restrict__ w,
                                                         const int* __restrict__ mask,
@@ -790,7 +791,7 @@ __global__ __launch_bounds__(KB2) void bmultidot_kernel(const ConfDev* __restric
     const int i = threadIdx.x + u * KB2;
     wr[u] = i < nr ? wp[i] : 0.0;
   }
-  const double* ap = A + cd.off + r0;
+  const TA* ap = A + cd.off + r0;
   double* out = partial + cd.kpoff + b.y;
   int k0 = 0, par = 0;
   for (; k0 + 8 <= kc; k0 += 8, par ^= 1)
@@ -828,12 +829,13 @@ __global__ void breduce_kernel(const ConfDev* __restrict__ cf, int nconf, int km
 // rows, ncols = jc[c] + 1 (Arnoldi) or kc[c] (solution update).  A thread keeps the sums
 // of its KU rows and loads two columns of all of them at once; each row's sum runs in k
 // order.
+template <typename TV>
 __global__ __launch_bounds__(KB2) void bupdate_kernel(const ConfDev* __restrict__ cf,
                                                       const int2* __restrict__ blk, int64_t T,
                                                       const int* __restrict__ mask,
                                                       const int* __restrict__ jc,
                                                       const int* __restrict__ kc,
-                                                      const double* __restrict__ V,
+                                                      const TV* __restrict__ V,
                                                       const double* __restrict__ h, int stride,
                                                       int off, double alpha,
                                                       double* __restrict__ w) {
@@ -845,7 +847,7 @@ __global__ __launch_bounds__(KB2) void bupdate_kernel(const ConfDev* __restrict_
   const int64_t r0 = (int64_t)b.y * KR;
   const int nr = (int)min((int64_t)KR, cd.N - r0);
   const double* hc = h + (int64_t)c * stride + off;
-  const double* vp = V + cd.off + r0;
+  const TV* vp = V + cd.off + r0;
   double* wp = w + cd.off + r0;
   int ir[KU];
   double sum[KU];
@@ -860,8 +862,8 @@ __global__ __launch_bounds__(KB2) void bupdate_kernel(const ConfDev* __restrict_
     double a0[KU], a1[KU];
 #pragma unroll
     for (int u = 0; u < KU; ++u) {
-      a0[u] = vp[(int64_t)k * T + ir[u]];
-      a1[u] = vp[(int64_t)(k + 1) * T + ir[u]];
+      a0[u] = (double)vp[(int64_t)k * T + ir[u]];
+      a1[u] = (double)vp[(int64_t)(k + 1) * T + ir[u]];
     }
     const double h0 = hc[k], h1 = hc[k + 1];
 #pragma unroll
@@ -870,7 +872,7 @@ __global__ __launch_bounds__(KB2) void bupdate_kernel(const ConfDev* __restrict_
   if (k < n) {
     const double h0 = hc[k];
 #pragma unroll
-    for (int u = 0; u < KU; ++u) sum[u] = fma(vp[(int64_t)k * T + ir[u]], h0, sum[u]);
+    for (int u = 0; u < KU; ++u) sum[u] = fma((double)vp[(int64_t)k * T + ir[u]], h0, sum[u]);
   }
 #pragma unroll
   for (int u = 0; u < KU; ++u) {
@@ -922,14 +924,16 @@ __global__ void bgivens_kernel(int nconf, int m, int* __restrict__ active, int* 
   }
 }
 
-// V[jc[c]*T + g] = w[g] * scale[c] on the block's rows.
+// V[jc[c]*T + g] = w[g] * scale[c] on the block's rows, and its FP32 copy in V32 when
+// given (the mixed solves' Gram-Schmidt passes read the copy).
 __global__ __launch_bounds__(KB2) void bscale_kernel(const ConfDev* __restrict__ cf,
                                                      const int2* __restrict__ blk, int64_t T,
                                                      const int* __restrict__ mask,
                                                      const int* __restrict__ jc,
                                                      const double* __restrict__ scale,
                                                      const double* __restrict__ w,
-                                                     double* __restrict__ V) {
+                                                     double* __restrict__ V,
+                                                     float* __restrict__ V32) {
   const int2 b = blk[blockIdx.x];
   const int c = b.x;
   if (!mask[c]) return;
@@ -938,8 +942,12 @@ __global__ __launch_bounds__(KB2) void bscale_kernel(const ConfDev* __restrict__
   const int nr = (int)min((int64_t)KR, cd.N - r0);
   const double sc = scale[c];
   const double* wp = w + cd.off + r0;
-  double* vp = V + (int64_t)jc[c] * T + cd.off + r0;
-  for (int i = threadIdx.x; i < nr; i += KB2) vp[i] = wp[i] * sc;
+  const int64_t o = (int64_t)jc[c] * T + cd.off + r0;
+  for (int i = threadIdx.x; i < nr; i += KB2) {
+    const double v = wp[i] * sc;
+    V[o + i] = v;
+    if (V32) V32[o + i] = (float)v;
+  }
 }
 
 // y = H^-1 g for the kc[c] columns of the finished cycle.
@@ -1236,6 +1244,12 @@ void Engine::rebuild() {
     YQ_HIP(hipGetLastError());
     if (used_ip) YQ_HIP(hipStreamSynchronize(stream));   // before the scratch buffer goes
   }
+  // the basis's FP32 copy for the mixed solves' Gram-Schmidt passes, out of what the
+  // caches left
+  if (prm.precision == YQ_MIXED)
+    V32.reserve((size_t)(m + 1) * std::max<int64_t>(T, 1));
+  else
+    V32.release();
   forest_in.build(tin, true, stream);
   forest_hi.build(thi, false, stream);
   conf.alloc(std::max(nc, 1));
@@ -1385,13 +1399,27 @@ void Engine::iteration_part(int prec, int part) {
   const int hs = 2 * (m + 1) + 2;
   matvec_part(NPART - 1, prec, active.p, V.p, jc.p, w.p);
   if (nkblk == 0) return;   // no configuration has nodes
+  // the mixed solves orthogonalise against the basis's FP32 copy (the Arnoldi relation
+  // then holds to FP32 rounding, far below the inner tolerance; the operator's input
+  // and the solution update use the FP64 basis)
+  const bool k32 = prec == YQ_MIXED && V32.p;
   for (int pass = 0; pass < 2; ++pass) {
-    bmultidot_kernel<<<nkblk, KB2, 0, stream>>>(conf.p, kblk.p, V.p, T, jc.p, w.p, active.p,
-                                                kpart.p);
+    if (k32)
+      bmultidot_kernel<<<nkblk, KB2, 0, stream>>>(conf.p, kblk.p, (const float*)V32.p, T, jc.p,
+                                                  w.p, active.p, kpart.p);
+    else
+      bmultidot_kernel<<<nkblk, KB2, 0, stream>>>(conf.p, kblk.p, (const double*)V.p, T, jc.p,
+                                                  w.p, active.p, kpart.p);
     breduce_kernel<<<nb256((int64_t)nc * (m + 1)), 256, 0, stream>>>(
         conf.p, nc, m + 1, jc.p, active.p, kpart.p, hb.p, hs, pass * (m + 1));
-    bupdate_kernel<<<nkblk, KB2, 0, stream>>>(conf.p, kblk.p, T, active.p, jc.p, nullptr, V.p,
-                                              hb.p, hs, pass * (m + 1), -1.0, w.p);
+    if (k32)
+      bupdate_kernel<<<nkblk, KB2, 0, stream>>>(conf.p, kblk.p, T, active.p, jc.p, nullptr,
+                                                (const float*)V32.p, hb.p, hs, pass * (m + 1),
+                                                -1.0, w.p);
+    else
+      bupdate_kernel<<<nkblk, KB2, 0, stream>>>(conf.p, kblk.p, T, active.p, jc.p, nullptr,
+                                                (const double*)V.p, hb.p, hs, pass * (m + 1),
+                                                -1.0, w.p);
   }
   bmultidot_kernel<<<nkblk, KB2, 0, stream>>>(conf.p, kblk.p, w.p, 0, nullptr, w.p, active.p,
                                               kpart.p);
@@ -1400,7 +1428,8 @@ void Engine::iteration_part(int prec, int part) {
   bgivens_kernel<<<nb256(nc), 256, 0, stream>>>(nc, m, active.p, jc.p, kc.p, hb.p, hs, H.p, cs.p,
                                                 sn.p, gv.p, scale.p, bnorm.p, rtol.p, res.p,
                                                 conv.p);
-  bscale_kernel<<<nkblk, KB2, 0, stream>>>(conf.p, kblk.p, T, active.p, jc.p, scale.p, w.p, V.p);
+  bscale_kernel<<<nkblk, KB2, 0, stream>>>(conf.p, kblk.p, T, active.p, jc.p, scale.p, w.p, V.p,
+                                           k32 ? V32.p : nullptr);
   YQ_HIP(hipGetLastError());
 }
 
@@ -1533,8 +1562,8 @@ void Engine::solve_cycle(const int* mask, double* x) {
   const int nc = (int)members.size();
   bsolve_kernel<<<nb256(nc), 256, 0, stream>>>(nc, m, mask, kc.p, H.p, gv.p, yv.p);
   if (nkblk)
-    bupdate_kernel<<<nkblk, KB2, 0, stream>>>(conf.p, kblk.p, T, mask, nullptr, kc.p, V.p, yv.p,
-                                              m, 0, 1.0, x);
+    bupdate_kernel<<<nkblk, KB2, 0, stream>>>(conf.p, kblk.p, T, mask, nullptr, kc.p,
+                                              (const double*)V.p, yv.p, m, 0, 1.0, x);
   YQ_HIP(hipGetLastError());
 }
 
@@ -1631,7 +1660,8 @@ void Engine::gmres(int prec, const double* b, double* x, const std::vector<int>&
     YQ_HIP(hipMemcpyAsync(bnorm.p, bnv.data(), nc * sizeof(double), hipMemcpyHostToDevice, stream));
     YQ_HIP(hipMemcpyAsync(rtol.p, rt.data(), nc * sizeof(double), hipMemcpyHostToDevice, stream));
     // V0 = r / beta
-    bscale_kernel<<<nkblk, KB2, 0, stream>>>(conf.p, kblk.p, T, active.p, jc.p, scale.p, r.p, V.p);
+    bscale_kernel<<<nkblk, KB2, 0, stream>>>(conf.p, kblk.p, T, active.p, jc.p, scale.p, r.p, V.p,
+                                             prec == YQ_MIXED ? V32.p : nullptr);
     YQ_HIP(hipGetLastError());
     // iterate: at most m steps; the mask retires converged configurations
     int left = nact;
@@ -1643,8 +1673,8 @@ void Engine::gmres(int prec, const double* b, double* x, const std::vector<int>&
     // cycle end: y = H^-1 g and x += V y for the cycle's participants
     upload_mask(inc, act);
     bsolve_kernel<<<nb256(nc), 256, 0, stream>>>(nc, m, inc.p, kc.p, H.p, gv.p, yv.p);
-    bupdate_kernel<<<nkblk, KB2, 0, stream>>>(conf.p, kblk.p, T, inc.p, nullptr, kc.p, V.p, yv.p, m,
-                                                 0, 1.0, x);
+    bupdate_kernel<<<nkblk, KB2, 0, stream>>>(conf.p, kblk.p, T, inc.p, nullptr, kc.p,
+                                              (const double*)V.p, yv.p, m, 0, 1.0, x);
     YQ_HIP(hipGetLastError());
     std::vector<int> hk(nc), hc(nc);
     YQ_HIP(hipMemcpyAsync(hk.data(), kc.p, nc * sizeof(int), hipMemcpyDeviceToHost, stream));

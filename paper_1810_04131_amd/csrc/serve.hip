@@ -69,14 +69,19 @@ __global__ void sstart_kernel(int ns, const int* __restrict__ slots, const doubl
   rtol[c] = rt[t];
 }
 
+// V0 = r scale (and its FP32 copy in V32 when given, for the mixed solves'
+// Gram-Schmidt passes).
 __global__ void sscale_kernel(const int* __restrict__ node_conf, int64_t T,
                               const int* __restrict__ mask, const double* __restrict__ scale,
-                              const double* __restrict__ r, double* __restrict__ V) {
+                              const double* __restrict__ r, double* __restrict__ V,
+                              float* __restrict__ V32) {
   const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (g >= T) return;
   const int c = node_conf[g];
   if (c < 0 || !mask[c]) return;
-  V[g] = r[g] * scale[c];
+  const double v = r[g] * scale[c];
+  V[g] = v;
+  if (V32) V32[g] = (float)v;
 }
 
 }  // namespace yq
@@ -565,7 +570,8 @@ int yq_server_step(yq_server* s, int32_t* completed, int32_t* running, int32_t* 
         for (int c : start_slots) st[c] = 1;
         e.upload_mask(e.inc, st);
         sscale_kernel<<<(unsigned)((e.T + 255) / 256), 256, 0, e.stream>>>(
-            e.node_conf.p, e.T, e.inc.p, e.scale.p, e.r.p, e.V.p);
+            e.node_conf.p, e.T, e.inc.p, e.scale.p, e.r.p, e.V.p,
+            s->prm.precision == YQ_MIXED ? e.V32.p : nullptr);
         YQ_HIP(hipGetLastError());
       }
     }
