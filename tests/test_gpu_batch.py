@@ -509,6 +509,26 @@ def test_batch_leaf_pass_timers_count_pairs_and_leave_results_unchanged():
     assert n >= max(i["matvecs_fp32"] for i in infos) and 0 < pairs <= n * p1
 
 
+def test_batch_qbx_fold_with_panels_left_out():
+    """QBX corrections folded into the near-field caches: with 16-node leaves many
+    window panels (80 nodes per target) reach past the leaf's P2P list, so the finish
+    applies those panels itself (the left-out list) while the rest ride in the cached
+    coefficients; the operators agree with the passes that evaluate every pair."""
+    _torch()
+    cfgs = _forest_configs()
+    prm = dict(panels_per_particle=P, qbx_order=ORDER, tol=1e-10, precision=1, fmm_leaf_max=16)
+    plain = _lane_batch(cfgs, True, near=0, **prm)
+    cached = _lane_batch(cfgs, True, near=-1, **prm)
+    assert cached.near_cache_info()[1:] == (2, 2)
+    x = np.random.default_rng(12).standard_normal(cached.total)
+    for prec, tol in ((yq.YQ_MIXED, 5e-6), (yq.YQ_FP64, 1e-12)):
+        a = _np(cached.apply_operator(x, prec))
+        b = _np(plain.apply_operator(x, prec))
+        for c in range(len(cfgs)):
+            s = slice(int(cached.offsets[c]), int(cached.offsets[c + 1]))
+            assert _rel(a[s], b[s]) < tol, (prec, c)
+
+
 def test_batch_leaves_over_64_nodes_stay_uncached():
     """The cached leaf pass hands a source leaf's densities to the lanes through one
     wavefront exchange (at most 64 nodes): trees built with larger leaves keep the
