@@ -351,34 +351,44 @@ __device__ double correction_left(int64_t i, int64_t N, int P, int win, const TW
   return corr;
 }
 
-__global__ void bfinish_kernel(const ConfDev* __restrict__ cf, const int* __restrict__ node_conf,
-                               int64_t T, const int* __restrict__ mask, int f32,
-                               const double* __restrict__ V, const int* __restrict__ col,
-                               double* __restrict__ out) {
-  const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (g >= T) return;
-  const int c = node_conf[g];
-  if (c < 0 || !mask[c]) return;
+// Over the kblk items (configuration c, KR rows from lb KR on; a masked-off
+// configuration's blocks return after one load): the configuration's descriptor is
+// uniform over the block, each thread finishes every KB2-th row.
+__global__ __launch_bounds__(KB2) void bfinish_kernel(const ConfDev* __restrict__ cf,
+                                                      const int2* __restrict__ blk, int64_t T,
+                                                      const int* __restrict__ mask, int f32,
+                                                      const double* __restrict__ V,
+                                                      const int* __restrict__ col,
+                                                      double* __restrict__ out) {
+  const int2 b = blk[blockIdx.x];
+  const int c = b.x;
+  if (!mask[c]) return;
   const ConfDev& cd = cf[c];
   const int64_t N = cd.N;
-  const int64_t i = g - cd.off;
+  const int64_t r0 = (int64_t)b.y * KR;
+  const int nr = (int)min((int64_t)KR, N - r0);
   const double* sg = V + (col ? (int64_t)col[c] * T : 0) + cd.off;
-  double s = 0.0;
-  if (!f32 || cd.fmm) {
-    for (int k = 0; k < cd.chunks; ++k) s += cd.part64[(int64_t)k * N + i];
-  } else {
-    for (int k = 0; k < cd.chunks32; ++k) s += (double)cd.part32[(int64_t)k * N + i];
+  const double scale = cd.kappa * cd.kappa / (2.0 * PI);
+  const bool fold = f32 ? cd.qfold32 : cd.qfold64;
+  for (int q = threadIdx.x; q < nr; q += KB2) {
+    const int64_t i = r0 + q;
+    double s = 0.0;
+    if (!f32 || cd.fmm) {
+      for (int k = 0; k < cd.chunks; ++k) s += cd.part64[(int64_t)k * N + i];
+    } else {
+      for (int k = 0; k < cd.chunks32; ++k) s += (double)cd.part32[(int64_t)k * N + i];
+    }
+    s *= scale;
+    if (fold) {   // the correction came with the tree's leaf pass (bleft_kernel adds the
+      out[cd.off + i] = s;   // panels left out)
+      continue;
+    }
+    // the inner (FP32) operator reads the correction in FP32 when it is there
+    const double corr =
+        f32 && cd.W32 ? correction_row(i, N, cd.P, cd.win, cd.W32, cd.xrow, cd.xpan, cd.xvals, sg)
+                      : correction_row(i, N, cd.P, cd.win, cd.W, cd.xrow, cd.xpan, cd.xvals, sg);
+    out[cd.off + i] = s + corr;
   }
-  s *= cd.kappa * cd.kappa / (2.0 * PI);
-  if (f32 ? cd.qfold32 : cd.qfold64) {   // the correction came with the tree's leaf pass
-    out[g] = s;                            // (bleft_kernel adds the panels left out)
-    return;
-  }
-  // the inner (FP32) operator reads the correction in FP32 when it is there
-  const double corr =
-      f32 && cd.W32 ? correction_row(i, N, cd.P, cd.win, cd.W32, cd.xrow, cd.xpan, cd.xvals, sg)
-                    : correction_row(i, N, cd.P, cd.win, cd.W, cd.xrow, cd.xpan, cd.xvals, sg);
-  out[g] = s + corr;
 }
 
 // The corrections of the panels left out of the QBX folds, after bfinish_kernel: items
@@ -1342,8 +1352,9 @@ void Engine::matvec_part(int part, int prec, const int* mask, const double* Vin,
       bfar64_kernel<<<grid_blocks(nitems), BB, 0, stream>>>(conf.p, items.p, nitems, mask, Vin, col, T,
                                                       tab64.p, pc);
   } else {
-    bfinish_kernel<<<nb256(T), 256, 0, stream>>>(conf.p, node_conf.p, T, mask, prec == YQ_MIXED,
-                                                 Vin, col, out);
+    if (nkblk)
+      bfinish_kernel<<<nkblk, KB2, 0, stream>>>(conf.p, kblk.p, T, mask, prec == YQ_MIXED, Vin,
+                                                col, out);
     if (nlitems)
       bleft_kernel<<<nb256(nlitems), 256, 0, stream>>>(conf.p, litems.p, nlitems, T, mask,
                                                        prec == YQ_MIXED, Vin, col, out);
@@ -1787,7 +1798,8 @@ void Engine::resid(const std::vector<int>& plain, const std::vector<int>& fused,
     bfused64_kernel<<<grid_blocks(nitems), BB, 0, stream>>>(conf.p, items.p, nitems, fmask.p, x, nullptr,
                                                       T, tab64.p);
   }
-  bfinish_kernel<<<nb256(T), 256, 0, stream>>>(conf.p, node_conf.p, T, inc.p, 0, x, nullptr, out);
+  if (nkblk)
+    bfinish_kernel<<<nkblk, KB2, 0, stream>>>(conf.p, kblk.p, T, inc.p, 0, x, nullptr, out);
   if (nlitems)
     bleft_kernel<<<nb256(nlitems), 256, 0, stream>>>(conf.p, litems.p, nlitems, T, inc.p, 0, x,
                                                      nullptr, out);
